@@ -1,0 +1,322 @@
+"""ctypes binding of the plain-C LCP oracle (lcp_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the benchmark's
+CPU-baseline leg.  The product library never imports this package and shares no
+code with it.  Every function here only marshals numpy arrays to the C oracle.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lcp_oracle.c")
+_LIB = os.path.join(_HERE, "liblcp_oracle.so")
+
+OK, ERR_ARG, ERR_EB_TOO_SMALL, ERR_RANGE, ERR_CAPACITY, ERR_CORRUPT, ERR_NO_REFERENCE = range(7)
+EB_ABS, EB_REL_GLOBAL, EB_REL_PER_FIELD = 0, 1, 2
+METHOD_AUTO, METHOD_S, METHOD_T = 0, 1, 2
+DECIDE_S, DECIDE_T, DECIDE_COMPARE = 1, 2, 3
+MAX_F = 8
+ALPHABET = 4148
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle with gcc (no contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(
+        os.path.getmtime(_SRC), os.path.getmtime(os.path.join(_HERE, "lcp_oracle.h"))
+    ):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(
+            ["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11", "-shared",
+             "-fPIC", "-o", tmp, _SRC, "-lm"]
+        )
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+class OracleError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        super().__init__(f"{what}: oracle status {status}")
+        self.status = status
+
+
+class Params(C.Structure):
+    _fields_ = [("eb_mode", C.c_int), ("eb", C.c_double), ("n_fields", C.c_int),
+                ("multi_frame", C.c_int), ("batch_size", C.c_int), ("block_log2", C.c_int),
+                ("chunk_log2", C.c_int)]
+
+
+class Grid(C.Structure):
+    _fields_ = [("m", C.c_float), ("eb_q", C.c_float), ("inv", C.c_double),
+                ("eb", C.c_double), ("E", C.c_int)]
+
+
+class Info(C.Structure):
+    _fields_ = [("mode", C.c_int), ("F", C.c_int), ("k", C.c_int), ("chunk_log2", C.c_int),
+                ("n_arrays", C.c_int), ("n", C.c_uint64), ("B", C.c_uint64),
+                ("total_bytes", C.c_uint64), ("seq", C.c_uint64), ("ref_seq", C.c_uint64),
+                ("bn", C.c_uint32 * 3), ("m", C.c_float * MAX_F), ("eb_q", C.c_float * MAX_F),
+                ("coder", C.c_int * (MAX_F + 2)), ("param", C.c_int * (MAX_F + 2)),
+                ("used", C.c_uint32 * (MAX_F + 2)), ("arr_n", C.c_uint64 * (MAX_F + 2)),
+                ("arr_off", C.c_uint64 * (MAX_F + 2)), ("arr_bytes", C.c_uint64 * (MAX_F + 2))]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = C.CDLL(build())
+        L = _lib
+        P = C.c_void_p
+        L.lco_extent.argtypes = [P, C.c_int, C.c_uint64, P, P]
+        L.lco_field_eb.argtypes = [C.c_int, C.c_double, C.c_int, P, P, P]
+        L.lco_make_grid.argtypes = [C.c_float, C.c_float, C.c_double, C.POINTER(Grid)]
+        L.lco_quant.argtypes = [C.c_float, C.POINTER(Grid)]
+        L.lco_quant.restype = C.c_int64
+        L.lco_recon.argtypes = [C.c_int64, C.POINTER(Grid)]
+        L.lco_recon.restype = C.c_float
+        L.lco_quantize.argtypes = [P, C.c_uint64, C.POINTER(Grid), P]
+        L.lco_quantize.restype = None
+        L.lco_reconstruct.argtypes = [P, C.c_uint64, C.POINTER(Grid), P]
+        L.lco_reconstruct.restype = None
+        L.lco_huffman_lengths.argtypes = [P, C.c_int, P]
+        L.lco_encode_array.argtypes = [P, C.c_uint64, C.c_int, P, C.c_uint64,
+                                       C.POINTER(C.c_uint64), C.POINTER(C.c_int),
+                                       C.POINTER(C.c_int), C.POINTER(C.c_uint32)]
+        L.lco_decode_array.argtypes = [P, C.c_uint64, C.c_uint64, C.c_int, C.c_int,
+                                       C.c_uint32, C.c_int, P]
+        L.lco_compress_s.argtypes = [P, C.c_int, C.c_uint64, P, C.c_int, C.c_int, C.c_uint64,
+                                     P, C.c_uint64, C.POINTER(C.c_uint64), P, P]
+        L.lco_compress_t.argtypes = [P, C.c_int, C.c_uint64, P, P, P, C.c_uint64, C.c_int,
+                                     C.c_uint64, P, C.c_uint64, C.POINTER(C.c_uint64), P]
+        L.lco_record_info.argtypes = [P, C.c_uint64, C.POINTER(Info)]
+        L.lco_decompress.argtypes = [P, C.c_uint64, P, C.c_uint64, C.c_uint64, P, C.c_uint64,
+                                     C.POINTER(C.c_uint64), P]
+        L.lco_stream_create.argtypes = [C.POINTER(Params), C.c_uint64]
+        L.lco_stream_create.restype = P
+        L.lco_stream_destroy.argtypes = [P]
+        L.lco_stream_destroy.restype = None
+        L.lco_stream_select.argtypes = [P, C.POINTER(C.c_int)]
+        L.lco_stream_compress.argtypes = [P, P, C.c_uint64, C.c_int, P, C.c_uint64,
+                                          C.POINTER(C.c_uint64), C.POINTER(C.c_int), P]
+        L.lco_stream_decompress.argtypes = [P, P, C.c_uint64, P, C.c_uint64,
+                                            C.POINTER(C.c_uint64)]
+        L.lco_search_k.argtypes = [P, C.c_int, C.c_uint64, C.POINTER(Params),
+                                   C.POINTER(C.c_int), P]
+        L.lco_bound.argtypes = [C.c_int, C.c_uint64, C.c_int]
+        L.lco_bound.restype = C.c_uint64
+    return _lib
+
+
+def _check(st: int, what: str):
+    if st != OK:
+        raise OracleError(st, what)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _fields(fields):
+    """List of contiguous float32 arrays + a C array of their pointers (kept alive)."""
+    arrs = [np.ascontiguousarray(f, dtype=np.float32) for f in fields]
+    ptrs = (C.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
+    return arrs, ptrs
+
+
+def _grids(grids):
+    arr = (Grid * len(grids))()
+    for i, g in enumerate(grids):
+        arr[i] = g
+    return arr
+
+
+# ---------------------------------------------------------------- steps
+def extent(fields):
+    arrs, ptrs = _fields(fields)
+    F = len(arrs)
+    lo = np.zeros(F, np.float32)
+    hi = np.zeros(F, np.float32)
+    _check(lib().lco_extent(ptrs, F, len(arrs[0]), _ptr(lo), _ptr(hi)), "extent")
+    return lo, hi
+
+
+def field_eb(eb_mode, eb, lo, hi):
+    F = len(lo)
+    lo = np.ascontiguousarray(lo, np.float32)
+    hi = np.ascontiguousarray(hi, np.float32)
+    out = np.zeros(F, np.float64)
+    _check(lib().lco_field_eb(eb_mode, eb, F, _ptr(lo), _ptr(hi), _ptr(out)), "field_eb")
+    return out
+
+
+def make_grid(lo, hi, eb_f) -> Grid:
+    g = Grid()
+    _check(lib().lco_make_grid(float(lo), float(hi), float(eb_f), C.byref(g)), "make_grid")
+    return g
+
+
+def quantize(x, g: Grid) -> np.ndarray:
+    x = np.ascontiguousarray(x, np.float32)
+    q = np.zeros(len(x), np.int64)
+    lib().lco_quantize(_ptr(x), len(x), C.byref(g), _ptr(q))
+    return q
+
+
+def reconstruct(q, g: Grid) -> np.ndarray:
+    q = np.ascontiguousarray(q, np.int64)
+    out = np.zeros(len(q), np.float32)
+    lib().lco_reconstruct(_ptr(q), len(q), C.byref(g), _ptr(out))
+    return out
+
+
+def huffman_lengths(counts) -> np.ndarray:
+    c = np.ascontiguousarray(counts, np.uint64)
+    ln = np.zeros(len(c), np.uint8)
+    lib().lco_huffman_lengths(_ptr(c), len(c), _ptr(ln))
+    return ln
+
+
+def encode_array(values, chunk_log2=10):
+    v = np.ascontiguousarray(values, np.uint64)
+    nb, coder, param, used = C.c_uint64(), C.c_int(), C.c_int(), C.c_uint32()
+    L = lib()
+    _check(L.lco_encode_array(_ptr(v), len(v), chunk_log2, None, 0, C.byref(nb),
+                              C.byref(coder), C.byref(param), C.byref(used)), "encode size")
+    out = np.zeros(max(nb.value, 1), np.uint8)
+    _check(L.lco_encode_array(_ptr(v), len(v), chunk_log2, _ptr(out), nb.value, C.byref(nb),
+                              C.byref(coder), C.byref(param), C.byref(used)), "encode")
+    return out[: nb.value].tobytes(), coder.value, param.value, used.value
+
+
+def decode_array(data: bytes, n, coder, param, used, chunk_log2=10) -> np.ndarray:
+    buf = np.frombuffer(data, np.uint8).copy() if len(data) else np.zeros(1, np.uint8)
+    v = np.zeros(max(n, 1), np.uint64)
+    _check(lib().lco_decode_array(_ptr(buf), len(data), n, coder, param, used, chunk_log2,
+                                  _ptr(v)), "decode_array")
+    return v[:n]
+
+
+def bound(F, n, chunk_log2=10) -> int:
+    return int(lib().lco_bound(F, n, chunk_log2))
+
+
+def grids_for(fields, eb_mode, eb):
+    lo, hi = extent(fields)
+    ebf = field_eb(eb_mode, eb, lo, hi)
+    return [make_grid(lo[f], hi[f], ebf[f]) for f in range(len(fields))]
+
+
+def compress_s(fields, grids, k, chunk_log2=10, seq=0):
+    arrs, ptrs = _fields(fields)
+    F, n = len(arrs), len(arrs[0])
+    cap = bound(F, n, chunk_log2)
+    out = np.zeros(cap, np.uint8)
+    perm = np.zeros(n, np.uint32)
+    q = np.zeros((F, n), np.int32)
+    size = C.c_uint64()
+    _check(lib().lco_compress_s(ptrs, F, n, _grids(grids), k, chunk_log2, seq, _ptr(out), cap,
+                                C.byref(size), _ptr(perm), _ptr(q)), "compress_s")
+    return out[: size.value].tobytes(), perm, q
+
+
+def compress_t(fields, grids, ref_perm, ref_q, ref_seq, chunk_log2=10, seq=1):
+    arrs, ptrs = _fields(fields)
+    F, n = len(arrs), len(arrs[0])
+    cap = bound(F, n, chunk_log2)
+    out = np.zeros(cap, np.uint8)
+    q = np.zeros((F, n), np.int32)
+    rp = np.ascontiguousarray(ref_perm, np.uint32)
+    rq = np.ascontiguousarray(ref_q, np.int32)
+    size = C.c_uint64()
+    _check(lib().lco_compress_t(ptrs, F, n, _grids(grids), _ptr(rp), _ptr(rq), ref_seq,
+                                chunk_log2, seq, _ptr(out), cap, C.byref(size), _ptr(q)),
+           "compress_t")
+    return out[: size.value].tobytes(), q
+
+
+def record_info(rec: bytes) -> Info:
+    buf = np.frombuffer(rec, np.uint8).copy()
+    info = Info()
+    _check(lib().lco_record_info(_ptr(buf), len(rec), C.byref(info)), "record_info")
+    return info
+
+
+def decompress(rec: bytes, ref_q=None, ref_seq=0):
+    """Returns (fields [F][n] float32 in slot order, q [F][n] int32)."""
+    info = record_info(rec)
+    F, n = info.F, info.n
+    buf = np.frombuffer(rec, np.uint8).copy()
+    outs = [np.zeros(n, np.float32) for _ in range(F)]
+    optrs = (C.c_void_p * F)(*[o.ctypes.data for o in outs])
+    q = np.zeros((F, n), np.int32)
+    nout = C.c_uint64()
+    if ref_q is not None:
+        rq = np.ascontiguousarray(ref_q, np.int32)
+        rqp, rn = _ptr(rq), rq.shape[1]
+    else:
+        rqp, rn = None, 0
+    _check(lib().lco_decompress(_ptr(buf), len(rec), rqp, ref_seq, rn, optrs, n, C.byref(nout),
+                                _ptr(q)), "decompress")
+    return outs, q
+
+
+def search_k(fields, eb_mode, eb, chunk_log2=10):
+    arrs, ptrs = _fields(fields)
+    p = Params(eb_mode, eb, len(arrs), 0, 0, 0, chunk_log2)
+    k = C.c_int()
+    sizes = np.zeros(17, np.uint64)
+    _check(lib().lco_search_k(ptrs, len(arrs), len(arrs[0]), C.byref(p), C.byref(k),
+                              _ptr(sizes)), "search_k")
+    return k.value, sizes
+
+
+class Stream:
+    """Alg. 1 multi-frame driver with LCP-FSM (compress and decompress sides)."""
+
+    def __init__(self, eb_mode, eb, n_fields=3, multi_frame=1, batch_size=16, block_log2=4,
+                 chunk_log2=10, max_n=1 << 20):
+        self.p = Params(eb_mode, eb, n_fields, multi_frame, batch_size, block_log2, chunk_log2)
+        self.F = n_fields
+        self.max_n = max_n
+        self.h = lib().lco_stream_create(C.byref(self.p), max_n)
+        if not self.h:
+            raise OracleError(ERR_ARG, "stream_create")
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().lco_stream_destroy(h)
+            self.h = None
+
+    def select(self) -> int:
+        d = C.c_int()
+        _check(lib().lco_stream_select(self.h, C.byref(d)), "select")
+        return d.value
+
+    def compress(self, fields, method=METHOD_AUTO):
+        arrs, ptrs = _fields(fields)
+        n = len(arrs[0])
+        cap = bound(self.F, n, self.p.chunk_log2)
+        out = np.zeros(cap, np.uint8)
+        size, used = C.c_uint64(), C.c_int()
+        perm = np.zeros(n, np.uint32)
+        _check(lib().lco_stream_compress(self.h, ptrs, n, method, _ptr(out), cap, C.byref(size),
+                                         C.byref(used), _ptr(perm)), "stream_compress")
+        return out[: size.value].tobytes(), used.value, perm
+
+    def decompress(self, rec: bytes):
+        info = record_info(rec)
+        buf = np.frombuffer(rec, np.uint8).copy()
+        outs = [np.zeros(info.n, np.float32) for _ in range(info.F)]
+        optrs = (C.c_void_p * info.F)(*[o.ctypes.data for o in outs])
+        nout = C.c_uint64()
+        _check(lib().lco_stream_decompress(self.h, _ptr(buf), len(rec), optrs, info.n,
+                                           C.byref(nout)), "stream_decompress")
+        return outs

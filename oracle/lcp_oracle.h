@@ -1,0 +1,132 @@
+/*
+ * lcp_oracle.h -- plain, slow, single-threaded CPU oracle of the LCP-S / LCP-T
+ * compressor (Zhang et al., "LCP: Enhancing Scientific Data Management with
+ * Lossy Compression for Particles", arXiv 2411.00761).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file and lcp_oracle.c exist to check the GPU
+ * library; only the tests, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no code, header or constant table with the
+ * HIP implementation under paper_2411_00761_amd/.
+ *
+ * Every entry point works on host memory and returns an lco status code.
+ * The byte format it writes is the frame record described in the design doc
+ * ("Frame record format"); the oracle is the executable definition of it.
+ */
+#ifndef LCP_ORACLE_H
+#define LCP_ORACLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LCO_OK = 0,
+  LCO_ERR_ARG = 1,
+  LCO_ERR_EB_TOO_SMALL = 2,
+  LCO_ERR_RANGE = 3,
+  LCO_ERR_CAPACITY = 4,
+  LCO_ERR_CORRUPT = 5,
+  LCO_ERR_NO_REFERENCE = 6,
+  LCO_ERR_BUDGET = 7,
+  LCO_ERR_DEVICE = 8
+};
+
+enum { LCO_EB_ABS = 0, LCO_EB_REL_GLOBAL = 1, LCO_EB_REL_PER_FIELD = 2 };
+enum { LCO_METHOD_AUTO = 0, LCO_METHOD_S = 1, LCO_METHOD_T = 2 };
+enum { LCO_DECIDE_S = 1, LCO_DECIDE_T = 2, LCO_DECIDE_COMPARE = 3 };
+
+#define LCO_MAX_F 8
+
+typedef struct {
+  int eb_mode;      /* LCO_EB_* */
+  double eb;        /* absolute bound, or the factor applied to the value range */
+  int n_fields;     /* 3 (xyz) .. 8; fields 3.. are supplementary */
+  int multi_frame;  /* 0: every frame spatial; 1: LCP-FSM chooses S/T */
+  int batch_size;   /* Alg. 1 batch length; 0 = one unbounded batch */
+  int block_log2;   /* k in [0,16]; p = 2^k quantisation bins per block side */
+  int chunk_log2;   /* Huffman chunk = 2^chunk_log2 symbols, in [5,16] */
+} lco_params;
+
+/* Quantisation grid of one field (Eq. 5 with the FP32 rounding margin). */
+typedef struct {
+  float m;       /* origin: the field's minimum on the frame that set the grid */
+  float eb_q;    /* half bin width actually used, eb_q <= eb - delta */
+  double inv;    /* 1 / (2 * eb_q), double, round-to-nearest */
+  double eb;     /* the user's absolute bound for this field */
+  int E;         /* magnitude exponent: every |x| + 2 eb < 2^E */
+} lco_grid;
+
+/* Decoded header of a frame record. */
+typedef struct {
+  int mode;            /* 0 = S, 1 = T */
+  int F, k, chunk_log2, n_arrays;
+  uint64_t n, B, total_bytes, seq, ref_seq;
+  uint32_t bn[3];
+  float m[LCO_MAX_F], eb_q[LCO_MAX_F];
+  int coder[LCO_MAX_F + 2];   /* 0 fixed, 1 Huffman */
+  int param[LCO_MAX_F + 2];   /* width w, or longest code length */
+  uint32_t used[LCO_MAX_F + 2];
+  uint64_t arr_n[LCO_MAX_F + 2], arr_off[LCO_MAX_F + 2], arr_bytes[LCO_MAX_F + 2];
+} lco_info;
+
+/* ---- step-level entry points (pins and parity at every step) ---- */
+int lco_extent(const float* const* x, int F, uint64_t n, float* lo, float* hi);
+int lco_field_eb(int eb_mode, double eb, int F, const float* lo, const float* hi,
+                 double* eb_f);
+int lco_make_grid(float lo, float hi, double eb_f, lco_grid* g);
+int64_t lco_quant(float x, const lco_grid* g);
+float lco_recon(int64_t q, const lco_grid* g);
+void lco_quantize(const float* x, uint64_t n, const lco_grid* g, int64_t* q);
+void lco_reconstruct(const int64_t* q, uint64_t n, const lco_grid* g, float* out);
+int lco_huffman_lengths(const uint64_t* counts, int K, uint8_t* len);
+/* Encode one symbol array as fixed or Huffman (whichever is shorter). Writes the
+ * array's data bytes to out (may be NULL to only size it). */
+int lco_encode_array(const uint64_t* v, uint64_t n, int chunk_log2, uint8_t* out,
+                     uint64_t cap, uint64_t* nbytes, int* coder, int* param,
+                     uint32_t* used);
+int lco_decode_array(const uint8_t* data, uint64_t nbytes, uint64_t n, int coder,
+                     int param, uint32_t used, int chunk_log2, uint64_t* v);
+
+/* ---- frame-level compressors ---- */
+/* LCP-S.  grids[F] must be made from this frame's extent.  perm (slot -> input
+ * index, [n]) and q_slot ([F][n], slot order) are optional outputs. */
+int lco_compress_s(const float* const* x, int F, uint64_t n, const lco_grid* grids,
+                   int k, int chunk_log2, uint64_t seq, uint8_t* out, uint64_t cap,
+                   uint64_t* size, uint32_t* perm, int32_t* q_slot);
+/* LCP-T against a reference (grids, slot permutation, slot-order codes). */
+int lco_compress_t(const float* const* x, int F, uint64_t n, const lco_grid* grids,
+                   const uint32_t* ref_perm, const int32_t* ref_q, uint64_t ref_seq,
+                   int chunk_log2, uint64_t seq, uint8_t* out, uint64_t cap,
+                   uint64_t* size, int32_t* q_slot);
+int lco_record_info(const uint8_t* rec, uint64_t size, lco_info* info);
+/* Decode a record.  T records need ref_q ([F][n] slot order) of the frame whose
+ * seq equals the record's ref_seq.  out[F] receive float32 in slot order;
+ * q_slot ([F][n]) optionally receives the codes. */
+int lco_decompress(const uint8_t* rec, uint64_t size, const int32_t* ref_q,
+                   uint64_t ref_seq, uint64_t ref_n, float* const* out, uint64_t cap_n,
+                   uint64_t* n_out, int32_t* q_slot);
+
+/* ---- multi-frame driver (Alg. 1 + LCP-FSM) ---- */
+typedef struct lco_stream lco_stream;
+lco_stream* lco_stream_create(const lco_params* p, uint64_t max_n);
+void lco_stream_destroy(lco_stream* s);
+int lco_stream_select(const lco_stream* s, int* decision);
+int lco_stream_compress(lco_stream* s, const float* const* x, uint64_t n, int method,
+                        uint8_t* out, uint64_t cap, uint64_t* size, int* method_used,
+                        uint32_t* perm_out);
+int lco_stream_decompress(lco_stream* s, const uint8_t* rec, uint64_t size,
+                          float* const* out, uint64_t cap_n, uint64_t* n_out);
+
+/* ---- block-size search ---- */
+int lco_search_k(const float* const* x, int F, uint64_t n, const lco_params* p,
+                 int* k_out, uint64_t* sizes /* [17], 0 = infeasible */);
+
+uint64_t lco_bound(int F, uint64_t n, int chunk_log2);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,159 @@
+"""Independent pure-Python reader of the LCP frame record (test helper).
+
+Written from the record layout stated in DESIGN.md ("Frame record format"), not
+from either implementation, so that a record written by the C oracle or by the GPU
+library can be taken apart and checked field by field.  Slow: small inputs only.
+"""
+from __future__ import annotations
+
+import struct
+
+MAGIC = b"LCP1"
+DIRECT = 4096
+FIRST_CLASS_BITS = 13
+MAX_LEN = 13
+
+
+class Bits:
+    """MSB-first reader over little-endian 32-bit words."""
+
+    def __init__(self, data: bytes, start_word: int, end_word: int):
+        self.words = struct.unpack_from("<%dI" % (end_word - start_word), data, 4 * start_word)
+        self.pos = 0
+        self.end = 32 * len(self.words)
+
+    def bit(self) -> int:
+        if self.pos >= self.end:
+            raise ValueError("read past end")
+        w = self.words[self.pos >> 5]
+        b = (w >> (31 - (self.pos & 31))) & 1
+        self.pos += 1
+        return b
+
+    def bits(self, n: int) -> int:
+        v = 0
+        for _ in range(n):
+            v = (v << 1) | self.bit()
+        return v
+
+
+def canonical(lengths: dict[int, int]) -> dict[int, tuple[int, int]]:
+    """symbol -> (code, length): shorter codes first, ties by symbol."""
+    order = sorted(lengths, key=lambda s: (lengths[s], s))
+    codes, code, prev = {}, 0, None
+    for s in order:
+        l = lengths[s]
+        if prev is not None:
+            code = (code + 1) << (l - prev)
+        else:
+            code = 0
+        codes[s] = (code, l)
+        prev = l
+    return codes
+
+
+def decode_array(data: bytes, n: int, coder: int, param: int, used: int, chunk_log2: int):
+    if coder == 0:
+        w = param
+        nwords = (n * w + 31) // 32
+        assert len(data) == 4 * nwords
+        r = Bits(data, 0, nwords)
+        return [r.bits(w) for _ in range(n)]
+    assert coder == 1
+    table = struct.unpack_from("<%dI" % used, data, 0)
+    lengths = {}
+    for e in table:
+        assert e >> 24 == 0
+        lengths[e & 0xFFFF] = (e >> 16) & 0xFF
+    assert list(lengths) == sorted(lengths)
+    assert max(lengths.values()) == param <= MAX_LEN
+    codes = canonical(lengths)
+    lookup = {(c, l): s for s, (c, l) in codes.items()}
+    C = 1 << chunk_log2
+    nchunks = (n + C - 1) // C
+    ends = struct.unpack_from("<%dI" % nchunks, data, 4 * used)
+    base = used + nchunks
+    payload_words = len(data) // 4 - base
+    assert len(data) % 4 == 0 and (nchunks == 0 or ends[-1] == payload_words)
+    out, start = [], 0
+    for c in range(nchunks):
+        r = Bits(data, base + start, base + ends[c])
+        for _ in range(min(C, n - c * C)):
+            code, l = 0, 0
+            while (code, l) not in lookup:
+                code = (code << 1) | r.bit()
+                l += 1
+                assert l <= MAX_LEN
+            s = lookup[(code, l)]
+            if s < DIRECT:
+                out.append(s)
+            else:
+                e = s - DIRECT + FIRST_CLASS_BITS - 1
+                out.append((1 << e) + r.bits(e))
+        start = ends[c]
+    return out
+
+
+def unzigzag(z: int) -> int:
+    return -(z >> 1) - 1 if z & 1 else z >> 1
+
+
+def parse(rec: bytes) -> dict:
+    """Header, grids, directory and the decoded symbol arrays of one record."""
+    assert rec[:4] == MAGIC
+    version, mode, F, k, cl, A, flags, hdr = struct.unpack_from("<HBBBBBBI", rec, 4)
+    n, B, total = struct.unpack_from("<QQQ", rec, 16)
+    bn = struct.unpack_from("<3I", rec, 40)
+    seq, ref_seq = struct.unpack_from("<QQ", rec, 56)
+    assert version == 1 and total == len(rec) and hdr == 80 + 8 * F + 32 * A
+    assert A == (F + 2 if mode == 0 else F)
+    grids = [struct.unpack_from("<ff", rec, 80 + 8 * f) for f in range(F)]
+    arrays, dirs, off = [], [], hdr
+    for a in range(A):
+        coder, param, _r, used, an, aoff, anb = struct.unpack_from("<BBHIQQQ", rec, 80 + 8 * F + 32 * a)
+        assert aoff == off
+        dirs.append(dict(coder=coder, param=param, used=used, n=an, off=aoff, nbytes=anb))
+        arrays.append(decode_array(rec[aoff:aoff + anb], an, coder, param, used, cl))
+        off += anb
+    assert off == total
+    return dict(mode=mode, F=F, k=k, chunk_log2=cl, n=n, B=B, bn=bn, seq=seq, ref_seq=ref_seq,
+                grids=grids, dirs=dirs, arrays=arrays)
+
+
+def s_codes(rec: bytes):
+    """Quantisation codes in slot order ([F][n] lists) of a spatial record, plus
+    the block ids and counts: inverse delta coding, block expansion, corner +
+    relative position."""
+    P = parse(rec)
+    assert P["mode"] == 0
+    F, n, k, B = P["F"], P["n"], P["k"], P["B"]
+    p = 1 << k
+    bnx, bny, _ = P["bn"]
+    ids, cnts, acc_id, acc_c = [], [], 0, 0
+    for b in range(B):
+        acc_id += P["arrays"][0][b]
+        acc_c += unzigzag(P["arrays"][1][b])
+        ids.append(acc_id)
+        cnts.append(acc_c)
+    q = [[0] * n for _ in range(F)]
+    rel = [0, 0, 0]
+    s = 0
+    for b in range(B):
+        i = ids[b]
+        corner = (i % bnx, (i // bnx) % bny, i // (bnx * bny))
+        for _ in range(cnts[b]):
+            for d in range(3):
+                rel[d] = (rel[d] + P["arrays"][2 + d][s]) % p
+                q[d][s] = corner[d] * p + rel[d]
+            s += 1
+    assert s == n
+    for f in range(3, F):
+        q[f] = list(P["arrays"][2 + f])
+    return q, ids, cnts, P
+
+
+def t_codes(rec: bytes, ref_q):
+    P = parse(rec)
+    assert P["mode"] == 1
+    return [[int(ref_q[f][s]) + unzigzag(P["arrays"][f][s]) for s in range(P["n"])]
+            for f in range(P["F"])], P
