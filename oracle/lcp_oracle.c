@@ -100,8 +100,10 @@ int lco_extent(const float* const* x, int F, uint64_t n, float* lo, float* hi) {
       if (v < a) a = v;
       if (v > b) b = v;
     }
-    lo[f] = a;
-    hi[f] = b;
+    /* -0 and +0 compare equal; the extent is taken as +0 so that the origin
+     * written to the record does not depend on which zero came first */
+    lo[f] = a == 0.0f ? 0.0f : a;
+    hi[f] = b == 0.0f ? 0.0f : b;
   }
   return LCO_OK;
 }
@@ -829,10 +831,15 @@ int lco_decompress(const uint8_t* rec, uint64_t size, const int32_t* ref_q,
     uint64_t rel[3] = {0, 0, 0};
     for (uint64_t b = 0; b < B && st == LCO_OK; b++) {
       /* inverse delta: running sums of ids and counts */
+      /* an id delta is at least 1 after the first block and below the id space,
+       * so the running id cannot wrap */
+      if ((b > 0 && v[0][b] == 0) || (unsigned __int128)v[0][b] >= tot) {
+        st = LCO_ERR_CORRUPT;
+        break;
+      }
       id += v[0][b];
-      c += unzigzag(v[1][b]);
-      if ((b > 0 && v[0][b] == 0) || (unsigned __int128)id >= tot || c < 1 ||
-          (uint64_t)c > n - s) {
+      c = (int64_t)((uint64_t)c + (uint64_t)unzigzag(v[1][b]));
+      if ((unsigned __int128)id >= tot || c < 1 || (uint64_t)c > n - s) {
         st = LCO_ERR_CORRUPT;
         break;
       }

@@ -440,3 +440,15 @@ def test_recursive_retrieval_matches_sequential_decode():
         out = part.decompress(recs[c])
     for d in range(3):
         assert np.array_equal(out[d], full[target][d])
+
+
+def test_signed_zero_extent_is_positive_zero():
+    """-0 and +0 are the same value; the origin written to the record is +0 either way."""
+    a = np.array([[-0.0, 1.0, 0.0], [0.0, 2.0, -0.0], [5.0, 6.0, 7.0]], np.float32)
+    lo, hi = O.extent(a)
+    assert np.signbit(lo[0]) == False and np.signbit(lo[1]) == False  # noqa: E712
+    b = a[:, ::-1].copy()
+    g1 = O.grids_for(a, O.EB_ABS, 0.01)
+    g2 = O.grids_for(b, O.EB_ABS, 0.01)
+    r1 = O.compress_s(a, g1, 2)[0]
+    assert fmt_ref.parse(r1)["grids"][0] == fmt_ref.parse(O.compress_s(b, g2, 2)[0])["grids"][0]
