@@ -1,0 +1,165 @@
+/*
+ * lcp.h -- C ABI of the MI355X (gfx950) LCP particle compressor.
+ *
+ * LCP (Zhang et al., arXiv 2411.00761) compresses frames of particle positions
+ * under a pointwise absolute error bound:
+ *   - LCP-S, the block-wise spatial compressor (Sec. 6): error-bound-aware
+ *     quantisation (Eq. 5), spatial blocks of 2^k bins per side (Eq. 6), the
+ *     non-empty blocks' ids / counts / corner-relative positions stored block by
+ *     block (Sec. 6.2.1), each array delta coded and then Huffman or fixed-length
+ *     coded, whichever is shorter (Sec. 6.2.2, Tab. 3);
+ *   - LCP-T, the temporal compressor (Sec. 7.1): codes on the reference frame's
+ *     grid minus the reference's codes;
+ *   - the multi-frame driver: LCP-FSM chooses S or T per frame (Sec. 7.2) and
+ *     Alg. 1 picks the reference (the last spatial anchor for the first frame of a
+ *     batch, otherwise the previous frame; Sec. 7.3);
+ *   - the block-size search over p = 2^k, 0 <= k <= 16, on a sample (Sec. 7.4.1).
+ * The problem statement (Sec. 4, Eq. 1-2) fixes the interface: particle arrays
+ * (frames x particles x coordinates, with further fields as supplementary
+ * dimensions), an absolute or value-range-relative error bound, and single- or
+ * multi-frame use.
+ *
+ * Conventions for every call:
+ *   - All particle and record buffers are DEVICE pointers owned by the caller
+ *     (e.g. the data pointers of torch tensors).  Fields are structure-of-arrays:
+ *     one float32 array of n values per field.
+ *   - Work is enqueued on the caller's hipStream_t (NULL = the null stream); the
+ *     calls that report sizes synchronise that stream before returning.
+ *   - Calls return an lcp_status; nothing crosses the ABI as an exception.  On an
+ *     error the output contents are undefined and the plan's stream state (the
+ *     reference frames and the FSM) is unchanged.
+ *   - A plan is one compression stream plus one decompression stream; it is not
+ *     thread-safe.  The plan owns all device scratch, allocated in lcp_plan.
+ *   - Decompressed particles come back in slot order (block order, stable in the
+ *     input index); lcp_compress can return the slot -> input index permutation.
+ */
+#ifndef LCP_H
+#define LCP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LCP_MAX_FIELDS 8
+
+typedef enum {
+  LCP_OK = 0,
+  LCP_ERR_ARG = 1,           /* invalid argument or non-finite input value */
+  LCP_ERR_EB_TOO_SMALL = 2,  /* eb below two float32 ulps of the data magnitude */
+  LCP_ERR_RANGE = 3,         /* codes would exceed 2^23, or block ids 2^63 */
+  LCP_ERR_CAPACITY = 4,      /* output buffer too small; required size reported */
+  LCP_ERR_CORRUPT = 5,       /* a record failed validation while decoding */
+  LCP_ERR_NO_REFERENCE = 6,  /* a temporal record's reference frame is not resident */
+  LCP_ERR_BUDGET = 7,        /* the plan's scratch would exceed hbm_budget_bytes */
+  LCP_ERR_DEVICE = 8         /* a HIP runtime call failed */
+} lcp_status;
+
+enum { LCP_EB_ABS = 0, LCP_EB_REL_GLOBAL = 1, LCP_EB_REL_PER_FIELD = 2 };
+enum { LCP_METHOD_AUTO = 0, LCP_METHOD_S = 1, LCP_METHOD_T = 2 };
+enum { LCP_DECIDE_S = 1, LCP_DECIDE_T = 2, LCP_DECIDE_COMPARE = 3 };
+
+typedef struct {
+  int eb_mode;        /* LCP_EB_ABS: eb is absolute.  LCP_EB_REL_GLOBAL: eb times the
+                         value range max(D)-min(D) over all fields (Sec. 4).
+                         LCP_EB_REL_PER_FIELD: eb times each field's own range. */
+  double eb;          /* > 0 */
+  int n_fields;       /* 3 (x, y, z) .. LCP_MAX_FIELDS; fields 3.. are supplementary */
+  int multi_frame;    /* 0: every frame LCP-S.  1: LCP-FSM picks S or T per frame and
+                         the error bound is fixed by the stream's first frame. */
+  int batch_size;     /* Alg. 1 batch length (frames); 0 = one unbounded batch */
+  int block_log2;     /* k in [0,16] (block side p = 2^k bins), or -1: search k on
+                         the sample given to lcp_plan (Sec. 7.4.1) */
+  int chunk_log2;     /* Huffman chunk of 2^chunk_log2 symbols, in [5,12]; a format
+                         parameter (10 by default when 0 is passed) */
+  uint64_t max_particles;    /* largest n per frame this plan will see (<= 2^31) */
+  uint64_t hbm_budget_bytes; /* 0 = unlimited; otherwise lcp_plan fails with
+                                LCP_ERR_BUDGET if its scratch would exceed it */
+  int device;                /* HIP device ordinal */
+} lcp_params;
+
+typedef struct lcp_plan_s* lcp_plan_t;
+
+/* One input frame: fields[0..n_fields) device pointers of n float32 values each. */
+typedef struct {
+  const float* fields[LCP_MAX_FIELDS];
+  uint64_t n;
+  int method; /* LCP_METHOD_AUTO (FSM), LCP_METHOD_S or LCP_METHOD_T */
+} lcp_frame_in;
+
+/* One compressed record in device memory. */
+typedef struct {
+  const void* data;
+  uint64_t size;
+} lcp_blob;
+
+/* Destination of one decompressed frame: n_fields device arrays of `capacity`
+ * float32 values each. */
+typedef struct {
+  float* fields[LCP_MAX_FIELDS];
+  uint64_t capacity;
+} lcp_frame_out;
+
+/* Create a plan: validates params, allocates all device scratch and the resident
+ * stream state on params->device, and, when block_log2 == -1, runs the
+ * block-size search on a stride sample of the given frame (sample_fields: device
+ * pointers, n_fields of them, sample_n values each; the stride is
+ * max(1, sample_n >> 20)).  The plan is returned in *out.
+ * Errors: LCP_ERR_ARG, LCP_ERR_BUDGET, LCP_ERR_DEVICE, and the search's errors. */
+lcp_status lcp_plan(const lcp_params* params, const float* const* sample_fields,
+                    uint64_t sample_n, lcp_plan_t* out);
+
+void lcp_plan_destroy(lcp_plan_t plan);
+
+/* The block size exponent k the plan uses (searched or given). */
+int lcp_plan_block_log2(lcp_plan_t plan);
+
+/* Worst-case record bytes for a frame of n particles. */
+uint64_t lcp_bound(lcp_plan_t plan, uint64_t n);
+
+/* Compress n_frames frames, in stream order, into out (device, out_cap bytes).
+ * Record j is written at out + out_offsets[j] and occupies
+ * out_offsets[j+1] - out_offsets[j] bytes (out_offsets: host array of
+ * n_frames + 1 entries; records are 4-byte aligned and back to back).
+ * methods_used (host, nullable): LCP_METHOD_S or LCP_METHOD_T per frame.
+ * perms (nullable; else n_frames device pointers, each nullable): receives the
+ * slot -> input index permutation of each frame (n uint32 values).
+ * In single-frame plans (multi_frame == 0) the frames are independent.
+ * Errors: LCP_ERR_ARG, LCP_ERR_EB_TOO_SMALL, LCP_ERR_RANGE, LCP_ERR_CAPACITY
+ * (out_offsets[n_frames] then holds the bytes required so far), LCP_ERR_DEVICE,
+ * LCP_ERR_NO_REFERENCE (LCP_METHOD_T without a resident reference). */
+lcp_status lcp_compress(lcp_plan_t plan, uint64_t n_frames, const lcp_frame_in* frames,
+                        void* out, uint64_t out_cap, uint64_t* out_offsets,
+                        int* methods_used, uint32_t* const* perms, hipStream_t stream);
+
+/* Decompress n_frames records, in stream order.  Frame j's float32 values are
+ * written, in slot order, to outs[j].fields[f][0..n); n_out (host) receives n.
+ * A temporal record needs its reference (the previous frame, or the last anchor
+ * for the first frame of a batch) decoded earlier by this plan.
+ * Errors: LCP_ERR_ARG, LCP_ERR_CORRUPT, LCP_ERR_NO_REFERENCE, LCP_ERR_CAPACITY
+ * (n_out then holds n), LCP_ERR_DEVICE. */
+lcp_status lcp_decompress(lcp_plan_t plan, uint64_t n_frames, const lcp_blob* blobs,
+                          const lcp_frame_out* outs, uint64_t* n_out, hipStream_t stream);
+
+/* What LCP-FSM decides for the next frame compressed with LCP_METHOD_AUTO:
+ * LCP_DECIDE_S, LCP_DECIDE_T or LCP_DECIDE_COMPARE (run both, keep the smaller). */
+lcp_status lcp_select(lcp_plan_t plan, int* decision);
+
+const char* lcp_status_string(lcp_status status);
+
+/* Kernel timing for roofline measurement: while a name is set, every launch of
+ * the kernel with that name is bracketed by HIP events on its stream; the
+ * accumulated time (ms), launch count and algorithmic bytes are read back with
+ * lcp_kernel_timer_read.  Pass NULL to stop. */
+lcp_status lcp_kernel_timer_set(lcp_plan_t plan, const char* kernel_name);
+lcp_status lcp_kernel_timer_read(lcp_plan_t plan, double* total_ms, uint64_t* launches,
+                                 uint64_t* bytes);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,541 @@
+// kernels_core.hip -- LCP-S / LCP-T data-parallel steps on gfx950:
+//   extent pass (min/max per field, the min(D.x) of Eq. 5),
+//   quantisation + block key (Eq. 5, Eq. 6),
+//   stable LSD radix sort of (block key, input index) -> block order (Sec. 6.2.1),
+//   device-wide scans, run detection (non-empty blocks), symbol arrays with delta
+//   coding (Sec. 6.2.2), temporal residuals (Sec. 7.1), and the decode-side block
+//   expansion and FP32 reconstruction.
+#include "lcp_internal.h"
+
+namespace lcp {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+inline uint32_t grid_for(uint64_t n, uint64_t per_block, uint32_t cap = 1u << 20) {
+  uint64_t g = (n + per_block - 1) / per_block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (uint32_t)g;
+}
+
+// ------------------------------------------------------------------ extent
+__global__ void k_extent_init(uint32_t* ext, int F, uint32_t* err) {
+  int t = threadIdx.x;
+  if (t < F) {
+    ext[2 * t] = 0xFFFFFFFFu;  // min key
+    ext[2 * t + 1] = 0u;       // max key
+  }
+  if (t == 0) *err = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_extent(FieldPtrs x, uint64_t n, uint32_t* ext,
+                                                     uint32_t* err) {
+  const int f = blockIdx.y;
+  const float* p = x.p[f];
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u, bad = 0u;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  // float4 body over the 16-byte aligned part, scalar head/tail
+  uint64_t head = (uint64_t)((16 - ((uintptr_t)p & 15)) & 15) / 4;
+  if (head > n) head = n;
+  uint64_t nv = (n - head) / 4;
+  const float4* p4 = reinterpret_cast<const float4*>(p + head);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
+    float4 v = p4[i];
+    float a[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      uint32_t key = float_key(a[j]);
+      mn = min(mn, key);
+      mx = max(mx, key);
+      bad |= !__builtin_isfinite(a[j]);
+    }
+  }
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < head + (n - head) % 4;
+       i += stride) {
+    uint64_t idx = i < head ? i : head + 4 * nv + (i - head);
+    float v = p[idx];
+    uint32_t key = float_key(v);
+    mn = min(mn, key);
+    mx = max(mx, key);
+    bad |= !__builtin_isfinite(v);
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    mn = min(mn, (uint32_t)__shfl_xor((int)mn, d, kWave));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, kWave));
+    bad |= (uint32_t)__shfl_xor((int)bad, d, kWave);
+  }
+  if (lane_id() == 0) {
+    atomicMin(&ext[2 * f], mn);
+    atomicMax(&ext[2 * f + 1], mx);
+    if (bad) atomicOr(err, kErrNonFinite);
+  }
+}
+
+// ------------------------------------------------------------------ quantise + key
+__global__ __launch_bounds__(kThreads) void k_quant_key(FieldPtrs x, uint64_t n, GridDev g,
+                                                        int k, uint64_t bn0, uint64_t bn1,
+                                                        uint64_t* keys, uint32_t* vals) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    uint64_t b0 = (uint64_t)quantise(x.p[0][i], g.m[0], g.inv[0]) >> k;
+    uint64_t b1 = (uint64_t)quantise(x.p[1][i], g.m[1], g.inv[1]) >> k;
+    uint64_t b2 = (uint64_t)quantise(x.p[2][i], g.m[2], g.inv[2]) >> k;
+    keys[i] = b0 + bn0 * (b1 + bn1 * b2);  // Eq. 6, x fastest
+    vals[i] = (uint32_t)i;
+  }
+}
+
+// ------------------------------------------------------------------ radix sort
+constexpr int kRsItems = 16;
+constexpr int kRsTile = kThreads * kRsItems;  // 4096 keys per tile
+
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint64_t* keys, uint64_t n,
+                                                         int shift, uint32_t* hist,
+                                                         uint32_t ntiles) {
+  __shared__ uint32_t cnt[kThreads / kWave][256];
+  const int t = threadIdx.x, w = wave_id();
+  for (int j = 0; j < 4; j++) cnt[j][t] = 0;
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * kRsTile;
+#pragma unroll 4
+  for (int j = 0; j < kRsItems; j++) {
+    uint64_t i = base + (uint64_t)j * kThreads + t;
+    if (i < n) atomicAdd(&cnt[w][(uint32_t)(keys[i] >> shift) & 255u], 1u);
+  }
+  __syncthreads();
+  hist[(uint64_t)t * ntiles + blockIdx.x] = cnt[0][t] + cnt[1][t] + cnt[2][t] + cnt[3][t];
+}
+
+// Stable scatter: elements keep their input order within a digit.  Each round
+// places 256 consecutive elements; a wave ranks equal digits by ballot (the 8
+// digit bits give each lane its set of peers) and waves are ordered by their
+// per-digit counts in LDS.
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* kin,
+                                                            const uint32_t* vin, uint64_t* kout,
+                                                            uint32_t* vout, uint64_t n,
+                                                            int shift, const uint32_t* offs,
+                                                            uint32_t ntiles) {
+  __shared__ uint32_t base[256];
+  __shared__ uint32_t wcnt[kThreads / kWave][256];
+  const int t = threadIdx.x, w = wave_id();
+  base[t] = offs[(uint64_t)t * ntiles + blockIdx.x];
+  const uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
+  const uint64_t lt = lanemask_lt();
+  for (int r = 0; r < kRsItems; r++) {
+    const uint64_t i = tile0 + (uint64_t)r * kThreads + t;
+    const bool valid = i < n;
+    uint64_t key = valid ? kin[i] : 0;
+    uint32_t val = valid ? vin[i] : 0;
+    uint32_t d = (uint32_t)(key >> shift) & 255u;
+#pragma unroll
+    for (int j = 0; j < kThreads / kWave; j++) wcnt[j][t] = 0;
+    __syncthreads();
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+      uint64_t bal = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? bal : ~bal;
+    }
+    uint32_t rank = (uint32_t)__popcll(peers & lt);
+    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t off = base[d] + rank;
+      for (int j = 0; j < w; j++) off += wcnt[j][d];
+      if (off < n) {
+        kout[off] = key;
+        vout[off] = val;
+      }
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int j = 0; j < kThreads / kWave; j++) add += wcnt[j][t];
+    base[t] += add;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ scans
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kThreads * kScanItems;  // 2048
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const T* in, uint64_t n,
+                                                          const uint32_t* n_dev, T* partials) {
+  uint64_t nn = n_dev ? min((uint64_t)*n_dev, n) : n;
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+  T s = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) {
+    uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
+    if (i < nn) s += in[i];
+  }
+  s = wave_sum(s);
+  __shared__ T sm[kThreads / kWave];
+  if (lane_id() == 0) sm[wave_id()] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T tot = 0;
+    for (int j = 0; j < kThreads / kWave; j++) tot += sm[j];
+    partials[blockIdx.x] = tot;
+  }
+}
+
+// Scan of one tile: striped load through LDS, blocked per-thread scan.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scan_apply(T* data, uint64_t n,
+                                                         const uint32_t* n_dev,
+                                                         const T* prefix, int exclusive) {
+  __shared__ T tile[kScanTile];
+  __shared__ T sm[kThreads / kWave + 1];
+  uint64_t nn = n_dev ? min((uint64_t)*n_dev, n) : n;
+  const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) {
+    uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
+    tile[j * kThreads + threadIdx.x] = i < nn ? data[i] : (T)0;
+  }
+  __syncthreads();
+  T v[kScanItems];
+  T local = 0;
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) {
+    v[j] = tile[threadIdx.x * kScanItems + j];
+    local += v[j];
+  }
+  T total;
+  T incl = block_incl_scan(local, sm, &total);
+  T run = incl - local + (prefix ? prefix[blockIdx.x] : (T)0);
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) {
+    if (exclusive) {
+      tile[threadIdx.x * kScanItems + j] = run;
+      run += v[j];
+    } else {
+      run += v[j];
+      tile[threadIdx.x * kScanItems + j] = run;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kScanItems; j++) {
+    uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
+    if (i < nn) data[i] = tile[j * kThreads + threadIdx.x];
+  }
+}
+
+// ------------------------------------------------------------------ runs
+// Non-empty blocks: a slot starts a block when its key differs from the previous
+// slot's.  flags_scan holds the inclusive count of block starts.
+__global__ __launch_bounds__(kThreads) void k_run_flags(const uint64_t* keys, uint64_t n,
+                                                        uint32_t* flags) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride)
+    flags[s] = (s == 0 || keys[s] != keys[s - 1]) ? 1u : 0u;
+}
+
+__global__ __launch_bounds__(kThreads) void k_runs_write(const uint64_t* keys,
+                                                         const uint32_t* scan, uint64_t n,
+                                                         uint64_t* ids, uint32_t* starts,
+                                                         uint32_t* B_dev) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
+    if (s == 0 || keys[s] != keys[s - 1]) {
+      uint32_t b = scan[s] - 1;
+      ids[b] = keys[s];
+      starts[b] = (uint32_t)s;
+    }
+    if (s == n - 1) *B_dev = scan[s];
+  }
+}
+
+// Delta coding of block ids and counts (Sec. 6.2.2): id deltas, zigzag of count
+// deltas.
+__global__ __launch_bounds__(kThreads) void k_block_syms(const uint64_t* ids,
+                                                         const uint32_t* starts,
+                                                         const uint32_t* B_dev, uint64_t n,
+                                                         uint64_t* v_id, uint64_t* v_cnt) {
+  const uint64_t B = *B_dev;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < B; b += stride) {
+    uint64_t id = ids[b];
+    v_id[b] = id - (b ? ids[b - 1] : 0);
+    int64_t c = (int64_t)((b + 1 < B ? (uint64_t)starts[b + 1] : n) - starts[b]);
+    int64_t cp = b ? (int64_t)(starts[b] - starts[b - 1]) : 0;
+    v_cnt[b] = zigzag64(c - cp);
+  }
+}
+
+// Slot-order symbols.  Each block of 256 threads covers 256 consecutive slots;
+// thread 0 also quantises the slot before the block so that every relative
+// position has its predecessor for the delta (mod p).
+__global__ __launch_bounds__(kThreads) void k_slot_syms(FieldPtrs x, int F, uint64_t n,
+                                                        GridDev g, int k, const uint32_t* perm,
+                                                        uint32_t* v_rel, uint32_t* v_sup,
+                                                        int32_t* q_slot) {
+  __shared__ uint32_t rel[3][kThreads + 1];
+  const uint64_t s0 = (uint64_t)blockIdx.x * kThreads;
+  const uint64_t s = s0 + threadIdx.x;
+  const uint32_t pm = (1u << k) - 1u;
+  const bool valid = s < n;
+  uint32_t i = valid ? perm[s] : 0;
+  if (valid) {
+    for (int f = 0; f < F; f++) {
+      int64_t q = quantise(x.p[f][i], g.m[f], g.inv[f]);
+      if (f < 3) rel[f][threadIdx.x + 1] = (uint32_t)q & pm;
+      else v_sup[(uint64_t)(f - 3) * n + s] = (uint32_t)q;
+      if (q_slot) q_slot[(uint64_t)f * n + s] = (int32_t)q;
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (s0 == 0) {
+      rel[0][0] = rel[1][0] = rel[2][0] = 0;
+    } else {
+      uint32_t ip = perm[s0 - 1];
+      for (int d = 0; d < 3; d++) rel[d][0] = (uint32_t)quantise(x.p[d][ip], g.m[d], g.inv[d]) & pm;
+    }
+  }
+  __syncthreads();
+  if (valid)
+    for (int d = 0; d < 3; d++)
+      v_rel[(uint64_t)d * n + s] = (rel[d][threadIdx.x + 1] - rel[d][threadIdx.x]) & pm;
+}
+
+// LCP-T: the frame's codes on the reference grid, in the reference's slot order,
+// minus the reference codes (zigzag); the new codes become the next reference.
+__global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64_t n, GridDev g,
+                                                      const uint32_t* perm_ref,
+                                                      const int32_t* q_ref, uint32_t* v_res,
+                                                      int32_t* q_new) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
+    uint32_t i = perm_ref[s];
+    for (int f = 0; f < F; f++) {
+      int64_t q = quantise(x.p[f][i], g.m[f], g.inv[f]);
+      int64_t r = q - (int64_t)q_ref[(uint64_t)f * n + s];
+      v_res[(uint64_t)f * n + s] = (uint32_t)zigzag64(r);
+      q_new[(uint64_t)f * n + s] = (int32_t)q;
+    }
+  }
+}
+
+// ------------------------------------------------------------------ decode side
+// Per block: validate id / count, corner of the block in quantisation bins, and
+// a start mark for the slot -> block expansion.  ids and cnt hold inclusive
+// scans of the decoded deltas; cum is the inclusive scan of the counts.
+__global__ __launch_bounds__(kThreads) void k_s_blocks(const uint64_t* ids,
+                                                       const uint64_t* cnt,
+                                                       const uint64_t* cum, uint64_t B,
+                                                       uint64_t n, uint64_t total_blocks,
+                                                       uint32_t bn0, uint32_t bn1, int k,
+                                                       uint32_t* corner, uint32_t* mark,
+                                                       uint32_t* err) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < B; b += stride) {
+    uint64_t id = ids[b];
+    uint64_t c = cnt[b];
+    bool bad = id >= total_blocks || (b > 0 && id <= ids[b - 1]) || c < 1 || c > n;
+    if (b == B - 1 && cum[b] != n) bad = true;
+    uint64_t start = cum[b] - c;
+    if (bad) {
+      atomicOr(err, kErrCorrupt);
+      continue;
+    }
+    uint64_t bx = id % bn0, rest = id / bn0;
+    uint64_t by = rest % bn1, bz = rest / bn1;
+    corner[b] = (uint32_t)(bx << k);
+    corner[B + b] = (uint32_t)(by << k);
+    corner[2 * B + b] = (uint32_t)(bz << k);
+    if (b > 0 && start < n) mark[start] = 1u;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_s_recon(const uint32_t* blk, const uint32_t* corner,
+                                                      uint64_t B, const uint32_t* rel,
+                                                      const uint32_t* sup, int F, uint64_t n,
+                                                      int k, GridDev g, OutPtrs out,
+                                                      int32_t* q_slot, uint32_t* err) {
+  const uint32_t pm = (1u << k) - 1u;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
+    uint64_t b = blk[s];
+    if (b >= B) {
+      atomicOr(err, kErrCorrupt);
+      continue;
+    }
+    for (int f = 0; f < F; f++) {
+      uint64_t q;
+      if (f < 3) q = (uint64_t)corner[(uint64_t)f * B + b] + (rel[(uint64_t)f * n + s] & pm);
+      else q = sup[(uint64_t)(f - 3) * n + s];
+      if (q >= (uint64_t)kQLimit) {
+        atomicOr(err, kErrCorrupt);
+        q = 0;
+      }
+      out.p[f][s] = reconstruct((int64_t)q, g.eb_q[f], g.m[f]);
+      if (q_slot) q_slot[(uint64_t)f * n + s] = (int32_t)q;
+    }
+  }
+}
+
+// LCP-T decode: q = q_ref + residual (residuals decoded as int32).
+__global__ __launch_bounds__(kThreads) void k_t_recon(const uint32_t* res, const int32_t* q_ref,
+                                                      int F, uint64_t n, GridDev g, OutPtrs out,
+                                                      int32_t* q_slot, uint32_t* err) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
+    for (int f = 0; f < F; f++) {
+      int64_t q = (int64_t)q_ref[(uint64_t)f * n + s] + (int64_t)(int32_t)res[(uint64_t)f * n + s];
+      if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
+        atomicOr(err, kErrCorrupt);
+        q = 0;
+      }
+      out.p[f][s] = reconstruct(q, g.eb_q[f], g.m[f]);
+      if (q_slot) q_slot[(uint64_t)f * n + s] = (int32_t)q;
+    }
+  }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+__global__ void k_copy_u32(const uint32_t* src, uint32_t* dst, uint64_t n) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = src[i];
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ launchers
+void launch_extent(const FieldPtrs& x, int F, uint64_t n, uint32_t* ext, uint32_t* err,
+                   hipStream_t s) {
+  k_extent_init<<<1, 64, 0, s>>>(ext, F, err);
+  dim3 grid(grid_for(n / 4 + 1, kThreads * 4, 1024), F);
+  LCP_TIMED("extent", (uint64_t)F * n * 4, s,
+            k_extent<<<grid, kThreads, 0, s>>>(x, n, ext, err));
+}
+
+void launch_quant_key(const FieldPtrs& x, uint64_t n, const GridDev& g, int k, uint64_t bn0,
+                      uint64_t bn1, uint64_t* keys, uint32_t* vals, hipStream_t s) {
+  LCP_TIMED("quant_key", n * (12 + 12), s,
+            k_quant_key<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(
+                x, n, g, k, bn0, bn1, keys, vals));
+}
+
+int radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint64_t n, int bits,
+               uint32_t* hist, uint32_t* tmp32, hipStream_t s) {
+  const uint32_t ntiles = (uint32_t)((n + kRsTile - 1) / kRsTile);
+  int cur = 0;
+  for (int shift = 0; shift < bits; shift += 8) {
+    uint64_t* kin = cur ? k1 : k0;
+    uint32_t* vin = cur ? v1 : v0;
+    uint64_t* kout = cur ? k0 : k1;
+    uint32_t* vout = cur ? v0 : v1;
+    k_radix_hist<<<ntiles, kThreads, 0, s>>>(kin, n, shift, hist, ntiles);
+    scan_device<uint32_t>(hist, (uint64_t)ntiles * 256, nullptr, true, tmp32, s);
+    LCP_TIMED("radix_scatter", n * 24, s,
+              k_radix_scatter<<<ntiles, kThreads, 0, s>>>(kin, vin, kout, vout, n, shift, hist,
+                                                          ntiles));
+    cur ^= 1;
+  }
+  return cur;
+}
+
+size_t scan_tmp_elems(uint64_t n) {
+  size_t t = 0;
+  uint64_t m = n;
+  while (m > (uint64_t)kScanTile) {
+    m = (m + kScanTile - 1) / kScanTile;
+    t += m;
+  }
+  return t + 16;
+}
+
+template <typename T>
+void scan_device(T* data, uint64_t n, const uint32_t* n_dev, bool exclusive, T* tmp,
+                 hipStream_t s) {
+  if (n == 0) return;
+  const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
+  if (tiles == 1) {
+    k_scan_apply<T><<<1, kThreads, 0, s>>>(data, n, n_dev, nullptr, exclusive ? 1 : 0);
+    return;
+  }
+  k_scan_reduce<T><<<(uint32_t)tiles, kThreads, 0, s>>>(data, n, n_dev, tmp);
+  scan_device<T>(tmp, tiles, nullptr, true, tmp + tiles, s);
+  k_scan_apply<T><<<(uint32_t)tiles, kThreads, 0, s>>>(data, n, n_dev, tmp, exclusive ? 1 : 0);
+}
+template void scan_device<uint32_t>(uint32_t*, uint64_t, const uint32_t*, bool, uint32_t*,
+                                    hipStream_t);
+template void scan_device<uint64_t>(uint64_t*, uint64_t, const uint32_t*, bool, uint64_t*,
+                                    hipStream_t);
+
+void launch_runs(const uint64_t* keys, uint64_t n, uint32_t* flags_scan, uint64_t* ids,
+                 uint32_t* starts, uint32_t* B_dev, uint32_t* tmp32, hipStream_t s) {
+  uint32_t g = grid_for(n, kThreads * 4, 1u << 16);
+  k_run_flags<<<g, kThreads, 0, s>>>(keys, n, flags_scan);
+  scan_device<uint32_t>(flags_scan, n, nullptr, false, tmp32, s);
+  k_runs_write<<<g, kThreads, 0, s>>>(keys, flags_scan, n, ids, starts, B_dev);
+}
+
+void launch_block_syms(const uint64_t* ids, const uint32_t* starts, const uint32_t* B_dev,
+                       uint64_t n, uint64_t* v_id, uint64_t* v_cnt, hipStream_t s) {
+  k_block_syms<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(ids, starts, B_dev, n,
+                                                                        v_id, v_cnt);
+}
+
+void launch_slot_syms(const FieldPtrs& x, int F, uint64_t n, const GridDev& g, int k,
+                      const uint32_t* perm, uint32_t* v_rel, uint32_t* v_sup, int32_t* q_slot,
+                      hipStream_t s) {
+  uint64_t bytes = n * (4 + 4ull * F + 4ull * F + (q_slot ? 4ull * F : 0));
+  LCP_TIMED("slot_syms", bytes, s,
+            k_slot_syms<<<(uint32_t)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
+                x, F, n, g, k, perm, v_rel, v_sup, q_slot));
+}
+
+void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
+                    const uint32_t* perm_ref, const int32_t* q_ref, uint32_t* v_res,
+                    int32_t* q_new, hipStream_t s) {
+  LCP_TIMED("t_resid", n * (4 + 16ull * F), s,
+            k_t_resid<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(
+                x, F, n, g, perm_ref, q_ref, v_res, q_new));
+}
+
+void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, uint64_t B,
+                     uint64_t n, uint64_t total_blocks, const uint32_t* bn, int k,
+                     uint32_t* corner, uint32_t* mark, uint32_t* err, hipStream_t s) {
+  k_s_blocks<<<grid_for(B, kThreads * 4, 1u << 16), kThreads, 0, s>>>(
+      ids, cnt, cum, B, n, total_blocks, bn[0], bn[1], k, corner, mark, err);
+}
+
+void launch_s_recon(const uint32_t* blk, const uint32_t* corner, uint64_t B,
+                    const uint32_t* rel, const uint32_t* sup, int F, uint64_t n, int k,
+                    const GridDev& g, const OutPtrs& out, int32_t* q_slot, uint32_t* err,
+                    hipStream_t s) {
+  LCP_TIMED("s_recon", n * (4 + 12 + 4ull * (F - 3) + 4ull * F + (q_slot ? 4ull * F : 0)), s,
+            k_s_recon<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(
+                blk, corner, B, rel, sup, F, n, k, g, out, q_slot, err));
+}
+
+void launch_t_recon(const uint32_t* res, const int32_t* q_ref, int F, uint64_t n,
+                    const GridDev& g, const OutPtrs& out, int32_t* q_slot, uint32_t* err,
+                    hipStream_t s) {
+  LCP_TIMED("t_recon", n * 16ull * F, s,
+            k_t_recon<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(
+                res, q_ref, F, n, g, out, q_slot, err));
+}
+
+void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (n) k_fill_u32<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(p, n, v);
+}
+
+void launch_copy_perm(const uint32_t* src, uint32_t* dst, uint64_t n, hipStream_t s) {
+  if (n) k_copy_u32<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(src, dst, n);
+}
+
+}  // namespace lcp

@@ -1,0 +1,126 @@
+// lcp_common.h -- format constants and wave64 device primitives shared by the
+// LCP HIP kernels (gfx950, 64-lane wavefronts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lcp {
+
+// ---- frame record layout (little-endian) ----
+constexpr uint32_t kMagic = 0x3150434Cu;  // bytes "LCP1"
+constexpr int kVersion = 1;
+constexpr int kHdrBytes = 80;
+constexpr int kDirBytes = 32;
+constexpr int kMaxF = 8;
+constexpr int kMaxArrays = kMaxF + 2;  // spatial record: ID, CNT, REL x/y/z, F-3 supplementary
+
+// ---- entropy coder ----
+// Values below kDirect are Huffman symbols themselves; a value v >= kDirect is
+// the symbol kDirect + bitwidth(v) - kFirstClassBits followed by its
+// bitwidth(v) - 1 low bits (the leading one is implied).
+constexpr int kDirect = 4096;
+constexpr int kFirstClassBits = 13;
+constexpr int kAlphabet = kDirect + 64 - kFirstClassBits + 1;  // 4148
+constexpr int kMaxLen = 13;                                     // longest Huffman code
+constexpr int kQLimit = 1 << 23;  // |2q+1| < 2^24: (float)(2q+1) is exact
+
+constexpr int kWave = 64;
+
+__host__ __device__ inline int bitwidth64(uint64_t v) {
+#ifdef __HIP_DEVICE_COMPILE__
+  return v ? 64 - __clzll((long long)v) : 0;
+#else
+  return v ? 64 - __builtin_clzll(v) : 0;
+#endif
+}
+
+__host__ __device__ inline uint64_t zigzag64(int64_t d) {
+  return d >= 0 ? (uint64_t)d << 1 : (((uint64_t)(-(d + 1))) << 1) | 1u;
+}
+__host__ __device__ inline int64_t unzigzag64(uint64_t z) {
+  return (z & 1) ? -(int64_t)(z >> 1) - 1 : (int64_t)(z >> 1);
+}
+
+// Huffman symbol of a value and the count of raw bits that follow its code.
+__device__ inline int symbol_of(uint64_t v, int* extra) {
+  if (v < (uint64_t)kDirect) {
+    *extra = 0;
+    return (int)v;
+  }
+  int b = bitwidth64(v);
+  *extra = b - 1;
+  return kDirect + b - kFirstClassBits;
+}
+
+// Eq. 5 on the device: floor(((double)x - (double)m) * inv), IEEE double, no
+// contraction (the build passes -ffp-contract=off).
+__device__ inline int64_t quantise(float x, float m, double inv) {
+  double t = ((double)x - (double)m) * inv;
+  return (int64_t)floor(t);
+}
+
+__device__ inline float reconstruct(int64_t q, float eb_q, float m) {
+  return __builtin_fmaf((float)(2 * q + 1), eb_q, m);
+}
+
+__device__ inline int lane_id() { return (int)(threadIdx.x & (kWave - 1)); }
+__device__ inline int wave_id() { return (int)(threadIdx.x / kWave); }
+__device__ inline uint64_t lanemask_lt() { return (1ull << lane_id()) - 1ull; }
+
+// Inclusive prefix sums across the 64 lanes of a wave.
+template <typename T>
+__device__ inline T wave_incl_scan(T v) {
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    T o = __shfl_up(v, d, kWave);
+    if (lane_id() >= d) v += o;
+  }
+  return v;
+}
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+// Inclusive block-wide scan; `sm` holds at least blockDim.x / 64 + 1 values.
+// Returns the inclusive prefix; *total receives the block total.
+template <typename T>
+__device__ inline T block_incl_scan(T v, T* sm, T* total) {
+  const int nw = (int)(blockDim.x / kWave);
+  T x = wave_incl_scan(v);
+  if (lane_id() == kWave - 1) sm[wave_id()] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    T run = 0;
+    for (int w = 0; w < nw; w++) {
+      T t = sm[w];
+      sm[w] = run;
+      run += t;
+    }
+    sm[nw] = run;
+  }
+  __syncthreads();
+  T r = x + sm[wave_id()];
+  *total = sm[nw];
+  __syncthreads();
+  return r;
+}
+
+// Sortable unsigned image of a float (monotone: a < b  <=>  key(a) < key(b)).
+__host__ __device__ inline uint32_t float_key(float f) {
+  uint32_t u;
+  __builtin_memcpy(&u, &f, 4);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__host__ __device__ inline float key_float(uint32_t k) {
+  uint32_t u = (k & 0x80000000u) ? (k & 0x7FFFFFFFu) : ~k;
+  float f;
+  __builtin_memcpy(&f, &u, 4);
+  return f;
+}
+
+}  // namespace lcp

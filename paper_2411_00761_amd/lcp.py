@@ -1,0 +1,209 @@
+"""Python binding of the LCP C ABI (include/lcp.h), same names as the C calls.
+
+Argument marshalling only: every step of compression and decompression runs in
+the HIP library liblcp_hip.so.  torch supplies device memory and the current HIP
+stream.  Loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblcp_hip.so")
+
+MAX_FIELDS = 8
+(OK, ERR_ARG, ERR_EB_TOO_SMALL, ERR_RANGE, ERR_CAPACITY, ERR_CORRUPT, ERR_NO_REFERENCE,
+ ERR_BUDGET, ERR_DEVICE) = range(9)
+EB_ABS, EB_REL_GLOBAL, EB_REL_PER_FIELD = 0, 1, 2
+METHOD_AUTO, METHOD_S, METHOD_T = 0, 1, 2
+DECIDE_S, DECIDE_T, DECIDE_COMPARE = 1, 2, 3
+
+EXPORTED = ["lcp_plan", "lcp_plan_destroy", "lcp_plan_block_log2", "lcp_bound", "lcp_compress",
+            "lcp_decompress", "lcp_select", "lcp_status_string", "lcp_kernel_timer_set",
+            "lcp_kernel_timer_read"]
+
+
+class LCPError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        msg = lib().lcp_status_string(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{what}: {msg} (status {status})")
+        self.status = status
+
+
+class lcp_params(C.Structure):
+    _fields_ = [("eb_mode", C.c_int), ("eb", C.c_double), ("n_fields", C.c_int),
+                ("multi_frame", C.c_int), ("batch_size", C.c_int), ("block_log2", C.c_int),
+                ("chunk_log2", C.c_int), ("max_particles", C.c_uint64),
+                ("hbm_budget_bytes", C.c_uint64), ("device", C.c_int)]
+
+
+class lcp_frame_in(C.Structure):
+    _fields_ = [("fields", C.c_void_p * MAX_FIELDS), ("n", C.c_uint64), ("method", C.c_int)]
+
+
+class lcp_blob(C.Structure):
+    _fields_ = [("data", C.c_void_p), ("size", C.c_uint64)]
+
+
+class lcp_frame_out(C.Structure):
+    _fields_ = [("fields", C.c_void_p * MAX_FIELDS), ("capacity", C.c_uint64)]
+
+
+_lib = None
+
+
+def lib():
+    """The loaded HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "(hipcc --offload-arch=gfx950); there is no fallback")
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.lcp_plan.argtypes = [C.POINTER(lcp_params), P, C.c_uint64, C.POINTER(P)]
+        L.lcp_plan_destroy.argtypes = [P]
+        L.lcp_plan_destroy.restype = None
+        L.lcp_plan_block_log2.argtypes = [P]
+        L.lcp_bound.argtypes = [P, C.c_uint64]
+        L.lcp_bound.restype = C.c_uint64
+        L.lcp_compress.argtypes = [P, C.c_uint64, P, P, C.c_uint64, P, P, P, P]
+        L.lcp_decompress.argtypes = [P, C.c_uint64, P, P, P, P]
+        L.lcp_select.argtypes = [P, C.POINTER(C.c_int)]
+        L.lcp_status_string.argtypes = [C.c_int]
+        L.lcp_status_string.restype = C.c_char_p
+        L.lcp_kernel_timer_set.argtypes = [P, C.c_char_p]
+        L.lcp_kernel_timer_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_uint64),
+                                            C.POINTER(C.c_uint64)]
+        _lib = L
+    return _lib
+
+
+def _stream_handle():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _check(st: int, what: str):
+    if st != OK:
+        raise LCPError(st, what)
+
+
+class Plan:
+    """lcp_plan / lcp_compress / lcp_decompress / lcp_select on one device.
+
+    frames are torch float32 CUDA tensors shaped (F, n) (rows contiguous)."""
+
+    def __init__(self, eb: float, eb_mode: int = EB_ABS, n_fields: int = 3,
+                 multi_frame: bool = False, batch_size: int = 16, block_log2: int = -1,
+                 chunk_log2: int = 10, max_particles: int = 1 << 20, hbm_budget_bytes: int = 0,
+                 device: int = 0, sample=None):
+        import torch
+        self.F = n_fields
+        self.device = device
+        self.params = lcp_params(eb_mode, eb, n_fields, int(multi_frame), batch_size, block_log2,
+                                 chunk_log2, max_particles, hbm_budget_bytes, device)
+        ptrs = None
+        sn = 0
+        if sample is not None:
+            sample = sample.contiguous()
+            ptrs = (C.c_void_p * n_fields)(*[sample[f].data_ptr() for f in range(n_fields)])
+            sn = sample.shape[1]
+        h = C.c_void_p()
+        with torch.cuda.device(device):
+            _check(lib().lcp_plan(C.byref(self.params), ptrs, sn, C.byref(h)), "lcp_plan")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lcp_plan_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def block_log2(self) -> int:
+        return lib().lcp_plan_block_log2(self.h)
+
+    def bound(self, n: int) -> int:
+        return int(lib().lcp_bound(self.h, n))
+
+    def select(self) -> int:
+        d = C.c_int()
+        _check(lib().lcp_select(self.h, C.byref(d)), "lcp_select")
+        return d.value
+
+    def compress(self, frames: Sequence, methods=None, want_perm: bool = False, out=None):
+        """Returns (out uint8 tensor, offsets list, methods_used list, perms list|None)."""
+        import torch
+        nf = len(frames)
+        frames = [f.contiguous() for f in frames]
+        arr = (lcp_frame_in * nf)()
+        cap = 0
+        for j, f in enumerate(frames):
+            assert f.dtype == torch.float32 and f.is_cuda and f.shape[0] == self.F
+            for k in range(self.F):
+                arr[j].fields[k] = f[k].data_ptr()
+            arr[j].n = f.shape[1]
+            arr[j].method = METHOD_AUTO if methods is None else methods[j]
+            cap += (self.bound(f.shape[1]) + 3) & ~3
+        if out is None:
+            out = torch.empty(max(cap, 4), dtype=torch.uint8, device=f"cuda:{self.device}")
+        offs = (C.c_uint64 * (nf + 1))()
+        used = (C.c_int * max(nf, 1))()
+        perms = None
+        pptr = None
+        if want_perm:
+            perms = [torch.empty(f.shape[1], dtype=torch.int32, device=f.device) for f in frames]
+            pptr = (C.c_void_p * nf)(*[p.data_ptr() for p in perms])
+        st = lib().lcp_compress(self.h, nf, arr, C.c_void_p(out.data_ptr()), out.numel(), offs, used,
+                                pptr, _stream_handle())
+        if st == ERR_CAPACITY:
+            raise LCPError(st, f"lcp_compress needs {offs[nf]} bytes")
+        _check(st, "lcp_compress")
+        return out, [int(offs[j]) for j in range(nf + 1)], [int(used[j]) for j in range(nf)], perms
+
+    def decompress(self, buf, offsets, sizes=None, outs=None):
+        """Decode records at buf[offsets[j]:offsets[j+1]]; returns (F, n) float32 tensors."""
+        import torch
+        nf = len(offsets) - 1
+        blobs = (lcp_blob * nf)()
+        for j in range(nf):
+            blobs[j].data = buf.data_ptr() + offsets[j]
+            blobs[j].size = (sizes[j] if sizes is not None else offsets[j + 1] - offsets[j])
+        if outs is None:
+            outs = []
+            for j in range(nf):
+                n = self.record_n(buf, offsets[j])
+                outs.append(torch.empty((self.F, n), dtype=torch.float32, device=buf.device))
+        fo = (lcp_frame_out * nf)()
+        for j, o in enumerate(outs):
+            for k in range(self.F):
+                fo[j].fields[k] = o[k].data_ptr()
+            fo[j].capacity = o.shape[1]
+        n_out = (C.c_uint64 * max(nf, 1))()
+        _check(lib().lcp_decompress(self.h, nf, blobs, fo, n_out, _stream_handle()),
+               "lcp_decompress")
+        return [o[:, : int(n_out[j])] for j, o in enumerate(outs)]
+
+    @staticmethod
+    def record_n(buf, offset: int) -> int:
+        """Particle count from a record header (bytes 16..23, little-endian)."""
+        b = buf[offset + 16: offset + 24].cpu().numpy().tobytes()
+        return int.from_bytes(b, "little")
+
+    def timer_set(self, name):
+        _check(lib().lcp_kernel_timer_set(self.h, None if name is None else name.encode()),
+               "lcp_kernel_timer_set")
+
+    def timer_read(self):
+        ms, la, by = C.c_double(), C.c_uint64(), C.c_uint64()
+        _check(lib().lcp_kernel_timer_read(self.h, C.byref(ms), C.byref(la), C.byref(by)),
+               "lcp_kernel_timer_read")
+        return ms.value, la.value, by.value

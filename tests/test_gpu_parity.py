@@ -1,0 +1,168 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle.
+
+Bit-exact on every record byte (which fixes the quantisation codes, block order,
+every symbol stream and coder choice), on the slot permutation, and on the
+decoded float32 values (0 ULP: both sides evaluate fmaf((float)(2q+1), eb_q, m)).
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import fmt_ref
+import oracle as O
+from paper_2411_00761_amd import datagen
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lcp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2411_00761_amd import lcp as L
+    L.lib()
+    return L
+
+
+def diff_report(got: bytes, want: bytes) -> str:
+    if got == want:
+        return "equal"
+    msg = [f"sizes {len(got)} vs {len(want)}"]
+    try:
+        a, b = fmt_ref.parse(got), fmt_ref.parse(want)
+        for key in ("mode", "n", "B", "k", "bn", "seq", "ref_seq", "grids"):
+            if a[key] != b[key]:
+                msg.append(f"{key}: {a[key]} vs {b[key]}")
+        for i, (da, db) in enumerate(zip(a["dirs"], b["dirs"])):
+            if da != db:
+                msg.append(f"array {i} dir {da} vs {db}")
+            if a["arrays"][i] != b["arrays"][i]:
+                j = next(t for t, (u, v) in enumerate(zip(a["arrays"][i], b["arrays"][i])) if u != v) \
+                    if len(a["arrays"][i]) == len(b["arrays"][i]) else -1
+                msg.append(f"array {i} values differ first at {j}")
+    except Exception as e:  # noqa: BLE001
+        msg.append(f"parse failed: {e!r}")
+    return "; ".join(msg)
+
+
+def bits_equal(a, b) -> bool:
+    return np.array_equal(np.asarray(a, np.float32).view(np.uint32), np.asarray(b, np.float32).view(np.uint32))
+
+
+def run_s(lcp, x, eb_mode, eb, k, chunk_log2=10):
+    plan = lcp.Plan(eb, eb_mode, n_fields=x.shape[0], block_log2=k, chunk_log2=chunk_log2,
+                    max_particles=x.shape[1])
+    xd = torch.from_numpy(x).cuda()
+    out, offs, used, perms = plan.compress([xd], want_perm=True)
+    torch.cuda.synchronize()
+    rec = out[offs[0]:offs[1]].cpu().numpy().tobytes()
+    dec = plan.decompress(out, offs)[0].cpu().numpy()
+    return rec, perms[0].cpu().numpy().astype(np.uint32), dec
+
+
+S_CASES = [
+    # (n, seed, hi, eb, k, chunk_log2)
+    (1, 1, 100.0, 1e-3, 4, 10),
+    (2, 2, 100.0, 1e-3, 0, 10),
+    (37, 3, 10.0, 0.05, 2, 5),
+    (1000, 4, 100.0, 1e-3, 10, 10),
+    (4097, 5, 100.0, 1e-3, 16, 10),
+    (65537, 6, 100.0, 1e-3, 8, 10),
+    (100000, 7, 1.0, 1e-4, 3, 9),
+]
+
+
+@pytest.mark.parametrize("n,seed,hi,eb,k,cl", S_CASES)
+def test_spatial_parity_uniform(lcp, n, seed, hi, eb, k, cl):
+    print(f"case n={n} seed={seed} k={k} cl={cl}", flush=True)
+    x = datagen.uniform_frame(n, hi=hi, seed=seed)
+    rec, perm, dec = run_s(lcp, x, lcp.EB_ABS, eb, k, cl)
+    grids = O.grids_for(x, O.EB_ABS, eb)
+    want, wperm, _ = O.compress_s(x, grids, k, cl, 0)
+    assert rec == want, diff_report(rec, want)
+    assert np.array_equal(perm, wperm)
+    wdec, _ = O.decompress(want)
+    for f in range(3):
+        assert bits_equal(dec[f], wdec[f])
+        assert np.max(np.abs(dec[f].astype(np.float64) - x[f][perm].astype(np.float64))) <= eb
+
+
+def test_spatial_parity_identical_points(lcp):
+    x = np.full((3, 5000), 7.25, np.float32)
+    x[:, 0] = 0.0
+    rec, perm, dec = run_s(lcp, x, lcp.EB_ABS, 0.01, 4)
+    want, wperm, _ = O.compress_s(x, O.grids_for(x, O.EB_ABS, 0.01), 4, 10, 0)
+    assert rec == want, diff_report(rec, want)
+    assert np.array_equal(perm, wperm)
+
+
+def test_spatial_parity_cosmology_six_fields(lcp):
+    x = datagen.cosmology_snapshot(200000, box=256.0, n_halos=50, seed=3)
+    rec, perm, dec = run_s(lcp, x, lcp.EB_REL_PER_FIELD, 1e-4, 3)
+    grids = O.grids_for(x, O.EB_REL_PER_FIELD, 1e-4)
+    want, wperm, _ = O.compress_s(x, grids, 3, 10, 0)
+    assert rec == want, diff_report(rec, want)
+    assert np.array_equal(perm, wperm)
+    wdec, _ = O.decompress(want)
+    for f in range(6):
+        assert bits_equal(dec[f], wdec[f])
+        assert np.max(np.abs(dec[f].astype(np.float64) - x[f][perm].astype(np.float64))) <= grids[f].eb
+
+
+def test_block_size_search_matches_oracle(lcp):
+    x = datagen.uniform_frame(1 << 18, seed=1)  # the 262,144-particle uniform frame, eb 1e-3
+    xd = torch.from_numpy(x).cuda()
+    plan = lcp.Plan(1e-3, lcp.EB_ABS, block_log2=-1, max_particles=x.shape[1], sample=xd)
+    k, sizes = O.search_k(x, O.EB_ABS, 1e-3)
+    assert plan.block_log2 == k
+    out, offs, _, perms = plan.compress([xd], want_perm=True)
+    rec = out[offs[0]:offs[1]].cpu().numpy().tobytes()
+    want, wperm, _ = O.compress_s(x, O.grids_for(x, O.EB_ABS, 1e-3), k, 10, 0)
+    assert rec == want, diff_report(rec, want)
+    assert len(rec) == int(sizes[k])
+    dec = plan.decompress(out, offs)[0].cpu().numpy()
+    wdec, _ = O.decompress(want)
+    assert all(bits_equal(dec[f], wdec[f]) for f in range(3))
+
+
+@pytest.mark.parametrize("batch", [4, 0])
+def test_multi_frame_stream_parity(lcp, batch):
+    n, frames = 50000, 12
+    traj = datagen.MDTrajectory(n, seed=21, step=0.002)
+    xs = [traj.next_frame() for _ in range(frames)]
+    ost = O.Stream(O.EB_REL_GLOBAL, 1e-4, batch_size=batch, block_log2=4, max_n=n)
+    plan = lcp.Plan(1e-4, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=batch, block_log2=4,
+                    max_particles=n)
+    dplan = lcp.Plan(1e-4, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=batch, block_log2=4,
+                     max_particles=n)
+    eb = 1e-4 * (float(xs[0].max()) - float(xs[0].min()))
+    for t, x in enumerate(xs):
+        assert plan.select() == ost.select(), t
+        want, wused, wperm = ost.compress(x)
+        out, offs, used, perms = plan.compress([torch.from_numpy(x).cuda()], want_perm=True)
+        rec = out[offs[0]:offs[1]].cpu().numpy().tobytes()
+        assert used[0] == wused, (t, used, wused)
+        assert rec == want, f"frame {t}: " + diff_report(rec, want)
+        assert np.array_equal(perms[0].cpu().numpy().astype(np.uint32), wperm)
+        dec = dplan.decompress(out, offs)[0].cpu().numpy()
+        wdec = ost.decompress(want)
+        for f in range(3):
+            assert bits_equal(dec[f], wdec[f]), (t, f)
+            assert np.max(np.abs(dec[f].astype(np.float64) - x[f][wperm].astype(np.float64))) <= eb
+
+
+def test_forced_temporal_identical_frame(lcp):
+    n = 30000
+    x = datagen.uniform_frame(n, seed=9)
+    plan = lcp.Plan(1e-3, lcp.EB_ABS, multi_frame=True, batch_size=0, block_log2=6, max_particles=n)
+    xd = torch.from_numpy(x).cuda()
+    out, offs, used, _ = plan.compress([xd, xd], methods=[lcp.METHOD_S, lcp.METHOD_T])
+    assert used == [lcp.METHOD_S, lcp.METHOD_T]
+    rec_t = out[offs[1]:offs[2]].cpu().numpy().tobytes()
+    P = fmt_ref.parse(rec_t)
+    assert P["mode"] == 1 and all(d["nbytes"] == 0 for d in P["dirs"])
+    dplan = lcp.Plan(1e-3, lcp.EB_ABS, multi_frame=True, batch_size=0, block_log2=6, max_particles=n)
+    d0, d1 = dplan.decompress(out, offs)
+    assert torch.equal(d0, d1)
