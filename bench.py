@@ -1,0 +1,211 @@
+"""Throughput benchmark of the LCP hot path on one MI355X.
+
+Default workload: the MD-like trajectory, 64 frames of 4,194,304 particles on a
+256x128x128 jittered lattice (spacing 1.0, jitter sigma 0.1, per-step Gaussian
+displacement sigma 0.01), float32 xyz, eb = 1e-4 x value range of the first
+frame, Alg. 1 batches of 16 frames with LCP-FSM choosing S or T per frame.
+
+One step = compress the 64 frames (one multi-frame stream) + decompress them
+(a second plan replays the stream).  The inputs are resident in HBM before the
+timed region.  Throughput follows Eq. 4: size(D) / time, size(D) = 4 * 3 * n
+bytes per frame.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import subprocess
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "compress/decompress GB/s at fixed eb + ratio; batched/served vs plain, p99"
+HBM_PEAK_GBPS = 8000.0
+
+# Algorithmic bytes per particle of the kernel the roofline is quoted on (see
+# DESIGN.md "Roofline accounting"): the temporal residual kernel reads the
+# frame (12 B), the reference codes (12 B) and the slot permutation (4 B), and
+# writes the residual symbols (12 B) and the new codes (12 B).
+ROOFLINE_KERNEL = "t_resid"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name"):
+                return line.split(":", 1)[1].strip()
+    except Exception:  # noqa: BLE001
+        pass
+    return platform.processor()
+
+
+def cpu_baseline(frames_np, eb_rel, batch, k, n_frames):
+    """The CPU oracle (single thread) on the first n_frames frames of the workload."""
+    import oracle as O
+    st = O.Stream(O.EB_REL_GLOBAL, eb_rel, batch_size=batch, block_log2=k,
+                  max_n=frames_np[0].shape[1])
+    dec = O.Stream(O.EB_REL_GLOBAL, eb_rel, batch_size=batch, block_log2=k,
+                   max_n=frames_np[0].shape[1])
+    t0 = time.perf_counter()
+    recs = [st.compress(frames_np[j])[0] for j in range(n_frames)]
+    t1 = time.perf_counter()
+    for r in recs:
+        dec.decompress(r)
+    t2 = time.perf_counter()
+    nbytes = sum(frames_np[j].nbytes for j in range(n_frames))
+    return dict(value=nbytes / (t2 - t0) / 1e9, unit="GB/s", cores=1, kind="oracle",
+                sample=f"first {n_frames} frames of the workload at full n, compress+decompress "
+                       f"(compress {nbytes / (t1 - t0) / 1e9:.4f} GB/s, decompress "
+                       f"{nbytes / (t2 - t1) / 1e9:.4f} GB/s), host CPU: {cpu_model()}, "
+                       f"nproc {os.cpu_count()}",
+                compress_s=t1 - t0, decompress_s=t2 - t1)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--frames", type=int, default=64)
+    ap.add_argument("--n", type=int, default=1 << 22)
+    ap.add_argument("--batch", type=int, default=16)
+    ap.add_argument("--eb", type=float, default=1e-4)
+    ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--roofline-kernel", default=ROOFLINE_KERNEL)
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1 "
+                                   "(multi-GPU sharding is a design note in DESIGN.md)"}))
+        sys.exit(2)
+
+    import torch
+
+    from paper_2411_00761_amd import datagen, lcp
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    nx, ny, nz = (256, 128, 128) if args.n == 1 << 22 else datagen.lattice_dims(args.n)
+    log(f"generating {args.frames} frames of {args.n} particles")
+    traj = datagen.MDTrajectory(args.n, dims=(nx, ny, nz), seed=2)
+    frames_np, frames = [], []
+    for j in range(args.frames):
+        f = traj.next_frame()
+        if j < args.cpu_frames:
+            frames_np.append(f)
+        frames.append(torch.from_numpy(f).to(dev))
+    torch.cuda.synchronize()
+    size_d = sum(f.numel() * 4 for f in frames)
+
+    plan = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=args.batch,
+                    block_log2=-1, max_particles=args.n, sample=frames[0])
+    k = plan.block_log2
+    dplan = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=args.batch,
+                     block_log2=k, max_particles=args.n)
+    log(f"block_log2 k={k}")
+    cap = sum((plan.bound(args.n) + 3) & ~3 for _ in frames)
+    outbuf = torch.empty(cap, dtype=torch.uint8, device=dev)
+    decbufs = [torch.empty((3, args.n), dtype=torch.float32, device=dev) for _ in range(args.frames)]
+
+    def step():
+        plan.reset()
+        dplan.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out, offs, used, _ = plan.compress(frames, out=outbuf)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        dplan.decompress(out, offs, outs=decbufs)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, offs, used
+
+    for w in range(args.warmup):
+        step()
+        log(f"warmup {w} done")
+    plan.timer_set(args.roofline_kernel)
+    dplan.timer_set(args.roofline_kernel)
+    tc = td = 0.0
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for s in range(args.steps):
+        c, d, offs, used = step()
+        tc += c
+        td += d
+        log(f"step {s}: compress {c * 1e3:.1f} ms, decompress {d * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t_start
+    kms, klaunch, kbytes = plan.timer_read()
+    dkms, dklaunch, dkbytes = dplan.timer_read()
+    kms, klaunch, kbytes = kms + dkms, klaunch + dklaunch, kbytes + dkbytes
+
+    comp_bytes = offs[-1]
+    ratio = size_d / comp_bytes
+    n_t = sum(1 for u in used if u == lcp.METHOD_T)
+    # error bound check on a few frames against the slot permutation
+    eb_abs = args.eb * (float(frames[0].max()) - float(frames[0].min()))
+    chk = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=args.batch, block_log2=k,
+                   max_particles=args.n)
+    out2, offs2, _, perms = chk.compress(frames[:3], want_perm=True)
+    dchk = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=args.batch,
+                    block_log2=k, max_particles=args.n)
+    dec = dchk.decompress(out2, offs2)
+    max_err = max(float((dec[j].double() - frames[j][:, perms[j].long()].double()).abs().max())
+                  for j in range(3))
+    assert max_err <= eb_abs, (max_err, eb_abs)
+
+    ms_per_step = t_total / args.steps * 1e3
+    achieved = (kbytes / klaunch) / (kms / klaunch * 1e-3) / 1e9 if klaunch else None
+    result = {
+        "metric": METRIC,
+        "value": size_d * args.steps / (tc + td) / 1e9,
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"MD-like trajectory, {args.frames} frames x {args.n} particles "
+                               f"({nx}x{ny}x{nz} lattice, jitter 0.1, step 0.01), float32 xyz, "
+                               f"eb={args.eb:g} x range, batch {args.batch}, LCP-FSM S/T",
+                   "frames": args.frames, "particles_per_frame": args.n, "block_log2": k,
+                   "chunk_log2": 10},
+        "compress_GBps": size_d * args.steps / tc / 1e9,
+        "decompress_GBps": size_d * args.steps / td / 1e9,
+        "ratio": ratio,
+        "bits_per_value": 32.0 / ratio,
+        "temporal_frames": n_t,
+        "max_abs_err": max_err,
+        "eb_abs": eb_abs,
+        "roofline": {"bound": "hbm", "kernel": args.roofline_kernel,
+                     "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": (achieved / HBM_PEAK_GBPS) if achieved else None,
+                     "traffic": None, "launches": klaunch,
+                     "avg_launch_us": (kms / klaunch * 1e3) if klaunch else None,
+                     "bytes_per_launch": (kbytes / klaunch) if klaunch else None},
+    }
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: oracle on {args.cpu_frames} frames")
+        cb = cpu_baseline(frames_np, args.eb, args.batch, k, args.cpu_frames)
+        result["cpu_baseline"] = {kk: cb[kk] for kk in ("value", "unit", "cores", "kind", "sample")}
+    print(json.dumps(result))
+
+
+if __name__ == "__main__":
+    main()

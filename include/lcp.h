@@ -115,6 +115,12 @@ lcp_status lcp_plan(const lcp_params* params, const float* const* sample_fields,
 
 void lcp_plan_destroy(lcp_plan_t plan);
 
+/* Forget the plan's stream state: both the compression and decompression sides
+ * restart at frame 0 with no reference frames, LCP-FSM back in S1X and (for
+ * multi-frame plans) the error bound taken again from the next frame.  Scratch
+ * and the block size are kept.  Returns LCP_ERR_ARG for a NULL plan. */
+lcp_status lcp_plan_reset(lcp_plan_t plan);
+
 /* The block size exponent k the plan uses (searched or given). */
 int lcp_plan_block_log2(lcp_plan_t plan);
 

@@ -1025,11 +1025,7 @@ int lco_stream_compress(lco_stream* s, const float* const* x, uint64_t n, int me
     st = lco_field_eb(s->p.eb_mode, s->p.eb, F, lo, hi, eb_f);
     if (st) return st;
   }
-  lco_grid sg[LCO_MAX_F];
-  for (int f = 0; f < F; f++) {
-    st = lco_make_grid(lo[f], hi[f], eb_f[f], &sg[f]);
-    if (st) return st;
-  }
+  lco_grid sg[LCO_MAX_F]; /* made only when LCP-S runs: a T frame needs no grid of its own */
   const ref_t* ref = s->p.multi_frame ? reference_for(&s->p, s->seq, &s->prev, &s->anchor)
                                       : NULL;
   if (ref && ref->n != n) ref = NULL;
@@ -1056,6 +1052,7 @@ int lco_stream_compress(lco_stream* s, const float* const* x, uint64_t n, int me
   }
   int need_s = decision != LCO_DECIDE_T || !have_t ||
                (method == LCO_METHOD_AUTO && size_tt > s->last_s);
+  for (int f = 0; f < F && st == LCO_OK && need_s; f++) st = lco_make_grid(lo[f], hi[f], eb_f[f], &sg[f]);
   if (st == LCO_OK && need_s) {
     bs = (uint8_t*)malloc(bound);
     perm_s = (uint32_t*)malloc(sizeof(uint32_t) * n);

@@ -41,6 +41,9 @@ __global__ __launch_bounds__(kThreads) void k_enc_init(ArrWork* W, ArrSet set) {
   }
 }
 
+// Lanes of a wave holding the same symbol are grouped by 13 ballots (one per
+// symbol bit); the lowest lane of each group adds the group's size, so a wave
+// of identical symbols (e.g. zero residuals) costs one LDS atomic, not 64.
 __global__ __launch_bounds__(kThreads) void k_hist(ArrSet set, ArrWork* W) {
   __shared__ uint32_t h[kAlphabet];
   const ArrIn a = set.a[blockIdx.y];
@@ -49,11 +52,22 @@ __global__ __launch_bounds__(kThreads) void k_hist(ArrSet set, ArrWork* W) {
   for (int j = threadIdx.x; j < kAlphabet; j += kThreads) h[j] = 0;
   __syncthreads();
   uint64_t mx = 0;
+  const uint64_t lt = lanemask_lt();
   const uint64_t stride = (uint64_t)gridDim.x * kThreads;
-  for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += stride) {
-    uint64_t v = arr_load(a, i);
+  for (uint64_t base = (uint64_t)blockIdx.x * kThreads + wave_id() * kWave; base < n;
+       base += stride) {
+    const uint64_t i = base + lane_id();
+    const bool valid = i < n;
+    uint64_t v = valid ? arr_load(a, i) : 0;
     int e;
-    atomicAdd(&h[symbol_of(v, &e)], 1u);
+    const uint32_t sym = (uint32_t)symbol_of(v, &e);
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 13; b++) {
+      uint64_t bal = __ballot((sym >> b) & 1u);
+      peers &= ((sym >> b) & 1u) ? bal : ~bal;
+    }
+    if (valid && (peers & lt) == 0) atomicAdd(&h[sym], (uint32_t)__popcll(peers));
     mx = v > mx ? v : mx;
   }
   __syncthreads();
@@ -567,11 +581,26 @@ __global__ void k_pack_huff(ArrSet set, const ArrWork* W, int chunk_log2, const 
 }
 
 // ------------------------------------------------------------------ decode
-__global__ __launch_bounds__(kHT) void k_lut(DecSet set, uint32_t* lut_all, uint32_t* err) {
+// Every array of every record in a call is described by a DecArr in device
+// memory.  Workgroups are assigned to arrays through a prefix of per-array
+// workgroup counts (binary search), so one launch decodes all arrays of all
+// frames: the entropy decoding of a batch does not depend on the reference
+// chain, only the reconstruction that follows does.
+__device__ inline uint32_t array_of_block(const uint32_t* prefix, int A, uint32_t b) {
+  int lo = 0, hi = A - 1;  // largest a with prefix[a] <= b
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return (uint32_t)lo;
+}
+
+__global__ __launch_bounds__(kHT) void k_lut(const DecArr* arrs, uint32_t* lut_all, uint32_t* err) {
   __shared__ uint32_t wcnt[kHT / kWave * 16];
   __shared__ uint32_t misc[64];
   const int a = blockIdx.x;
-  const DecArr d = set.a[a];
+  const DecArr d = arrs[a];
   if (d.coder != 1) return;
   const int t = threadIdx.x;
   const uint32_t U = d.used;
@@ -585,15 +614,15 @@ __global__ __launch_bounds__(kHT) void k_lut(DecSet set, uint32_t* lut_all, uint
   for (uint32_t i = t; i < (1u << L); i += kHT) lut[i] = 0;
   if (t < 64) misc[t] = 0;
   __syncthreads();
-  uint32_t* blc = misc;       // [16]
+  uint32_t* blc = misc;  // [16]
   uint32_t* first = misc + 16;
   uint32_t* run = misc + 32;
-  uint32_t* flags = misc + 48;  // [0] corrupt, [1] has length L, [2] kraft sum
+  uint32_t* flags = misc + 48;  // [0] malformed entry, [1] has length L, [2] Kraft sum
   for (uint32_t j = t; j < U; j += kHT) {
     uint32_t e = tab[j];
-    uint32_t s = e & 0xFFFFu, l = (e >> 16) & 0xFFu;
-    bool bad = (e >> 24) != 0 || s >= (uint32_t)kAlphabet || l < 1 || l > (uint32_t)L ||
-               (j > 0 && (tab[j - 1] & 0xFFFFu) >= s);
+    uint32_t sy = e & 0xFFFFu, l = (e >> 16) & 0xFFu;
+    bool bad = (e >> 24) != 0 || sy >= (uint32_t)kAlphabet || l < 1 || l > (uint32_t)L ||
+               (j > 0 && (tab[j - 1] & 0xFFFFu) >= sy);
     if (bad) atomicOr(&flags[0], 1u);
     else {
       atomicAdd(&blc[l], 1u);
@@ -660,19 +689,22 @@ __device__ inline bool store_value(const DecArr& d, uint64_t i, uint64_t v) {
 }
 
 // One thread per chunk; the array's lookup table is staged in LDS.
-__global__ __launch_bounds__(kThreads) void k_decode_huff(DecSet set, const uint32_t* lut_all,
+__global__ __launch_bounds__(kThreads) void k_decode_huff(const DecArr* arrs,
+                                                          const uint32_t* prefix, int A,
+                                                          int chunk_log2,
+                                                          const uint32_t* lut_all,
                                                           uint32_t* err) {
   __shared__ uint32_t lut[1u << kMaxLen];
-  const int a = blockIdx.y;
-  const DecArr d = set.a[a];
+  const uint32_t a = array_of_block(prefix, A, blockIdx.x);
+  const DecArr d = arrs[a];
   if (d.coder != 1 || d.param < 1 || d.param > kMaxLen || (*err & kErrCorrupt)) return;
   const int L = d.param;
   const uint32_t* src = lut_all + (uint64_t)a * (1u << kMaxLen);
   for (uint32_t i = threadIdx.x; i < (1u << L); i += kThreads) lut[i] = src[i];
   __syncthreads();
-  const uint64_t C = 1ull << set.chunk_log2;
-  const uint64_t nchunks = (d.n + C - 1) >> set.chunk_log2;
-  const uint64_t c = (uint64_t)blockIdx.x * kThreads + threadIdx.x;
+  const uint64_t C = 1ull << chunk_log2;
+  const uint64_t nchunks = (d.n + C - 1) >> chunk_log2;
+  const uint64_t c = (uint64_t)(blockIdx.x - prefix[a]) * kThreads + threadIdx.x;
   if (c >= nchunks) return;
   const uint32_t* offs = reinterpret_cast<const uint32_t*>(d.data) + d.used;
   const uint32_t* payload = offs + nchunks;
@@ -731,15 +763,19 @@ __global__ __launch_bounds__(kThreads) void k_decode_huff(DecSet set, const uint
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_decode_fixed(DecSet set, uint32_t* err) {
-  const int a = blockIdx.y;
-  const DecArr d = set.a[a];
+constexpr int kFixedPerBlock = kThreads * 4;
+
+__global__ __launch_bounds__(kThreads) void k_decode_fixed(const DecArr* arrs,
+                                                           const uint32_t* prefix, int A,
+                                                           uint32_t* err) {
+  const uint32_t a = array_of_block(prefix, A, blockIdx.x);
+  const DecArr d = arrs[a];
   if (d.coder != 0) return;
   const uint64_t w = (uint64_t)d.param;
   const uint64_t nwords = (d.n * w + 31) / 32;
   const uint32_t* src = reinterpret_cast<const uint32_t*>(d.data);
-  const uint64_t stride = (uint64_t)gridDim.x * kThreads;
-  for (uint64_t i = (uint64_t)blockIdx.x * kThreads + threadIdx.x; i < d.n; i += stride) {
+  const uint64_t i0 = (uint64_t)(blockIdx.x - prefix[a]) * kFixedPerBlock;
+  for (uint64_t i = i0 + threadIdx.x; i < d.n && i < i0 + kFixedPerBlock; i += kThreads) {
     uint64_t v = 0;
     if (w) {
       const uint64_t pos = i * w, w0 = pos >> 5;
@@ -799,22 +835,28 @@ void launch_encode(const ArrSet& set, uint64_t max_n, int chunk_log2, ArrWork* w
   }
 }
 
-void launch_decode(const DecSet& set, uint64_t max_n, uint64_t max_chunks, uint32_t* lut,
-                   uint32_t* err, hipStream_t s) {
-  (void)max_chunks;
-  const int A = set.A;
-  k_lut<<<A, kHT, 0, s>>>(set, lut, err);
-  const uint64_t chunks = (max_n + (1ull << set.chunk_log2) - 1) >> set.chunk_log2;
-  {
-    dim3 g(gclamp((chunks + kThreads - 1) / kThreads, 1u << 30), A);
-    LCP_TIMED("decode_huff", max_n * 6ull * A, s,
-              k_decode_huff<<<g, kThreads, 0, s>>>(set, lut, err));
+uint32_t decode_blocks(const DecArr& d, int chunk_log2, bool huff) {
+  if (huff) {
+    if (d.coder != 1) return 0;
+    uint64_t nchunks = (d.n + (1ull << chunk_log2) - 1) >> chunk_log2;
+    return (uint32_t)((nchunks + kThreads - 1) / kThreads);
   }
-  {
-    dim3 g(gclamp((max_n + 4 * kThreads - 1) / (4 * kThreads), 1u << 16), A);
-    LCP_TIMED("decode_fixed", max_n * 6ull * A, s,
-              k_decode_fixed<<<g, kThreads, 0, s>>>(set, err));
-  }
+  if (d.coder != 0) return 0;
+  return (uint32_t)((d.n + kFixedPerBlock - 1) / kFixedPerBlock);
+}
+
+void launch_decode(const DecArr* arrs_dev, int A, const uint32_t* huff_prefix_dev,
+                   uint32_t huff_blocks, const uint32_t* fixed_prefix_dev, uint32_t fixed_blocks,
+                   int chunk_log2, uint64_t bytes, uint32_t* lut, uint32_t* err, hipStream_t s) {
+  if (A == 0) return;
+  k_lut<<<A, kHT, 0, s>>>(arrs_dev, lut, err);
+  if (huff_blocks)
+    LCP_TIMED("decode_huff", bytes, s,
+              k_decode_huff<<<huff_blocks, kThreads, 0, s>>>(arrs_dev, huff_prefix_dev, A,
+                                                            chunk_log2, lut, err));
+  if (fixed_blocks)
+    LCP_TIMED("decode_fixed", bytes, s,
+              k_decode_fixed<<<fixed_blocks, kThreads, 0, s>>>(arrs_dev, fixed_prefix_dev, A, err));
 }
 
 }  // namespace lcp

@@ -21,17 +21,14 @@ inline uint32_t grid_for(uint64_t n, uint64_t per_block, uint32_t cap = 1u << 20
 }
 
 // ------------------------------------------------------------------ extent
-__global__ void k_extent_init(uint32_t* ext, int F, uint32_t* err) {
-  int t = threadIdx.x;
-  if (t < F) {
-    ext[2 * t] = 0xFFFFFFFFu;  // min key
-    ext[2 * t + 1] = 0u;       // max key
-  }
-  if (t == 0) *err = 0;
-}
+// Two passes: every block reduces its share of one field to a (min, max) pair
+// of sortable keys, then one block per field reduces the partials (no contended
+// atomics on a single address).
+constexpr int kExtBlocks = 256;
 
-__global__ __launch_bounds__(kThreads) void k_extent(FieldPtrs x, uint64_t n, uint32_t* ext,
+__global__ __launch_bounds__(kThreads) void k_extent(FieldPtrs x, uint64_t n, uint32_t* part,
                                                      uint32_t* err) {
+  __shared__ uint32_t smn[kThreads / kWave], smx[kThreads / kWave];
   const int f = blockIdx.y;
   const float* p = x.p[f];
   uint32_t mn = 0xFFFFFFFFu, mx = 0u, bad = 0u;
@@ -68,9 +65,47 @@ __global__ __launch_bounds__(kThreads) void k_extent(FieldPtrs x, uint64_t n, ui
     bad |= (uint32_t)__shfl_xor((int)bad, d, kWave);
   }
   if (lane_id() == 0) {
-    atomicMin(&ext[2 * f], mn);
-    atomicMax(&ext[2 * f + 1], mx);
+    smn[wave_id()] = mn;
+    smx[wave_id()] = mx;
     if (bad) atomicOr(err, kErrNonFinite);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / kWave; w++) {
+      mn = min(mn, smn[w]);
+      mx = max(mx, smx[w]);
+    }
+    part[2 * ((uint64_t)f * gridDim.x + blockIdx.x)] = mn;
+    part[2 * ((uint64_t)f * gridDim.x + blockIdx.x) + 1] = mx;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_extent_final(const uint32_t* part, int nblocks,
+                                                           uint32_t* ext) {
+  const int f = blockIdx.x;
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+  for (int b = threadIdx.x; b < nblocks; b += kThreads) {
+    mn = min(mn, part[2 * (f * nblocks + b)]);
+    mx = max(mx, part[2 * (f * nblocks + b) + 1]);
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    mn = min(mn, (uint32_t)__shfl_xor((int)mn, d, kWave));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, kWave));
+  }
+  __shared__ uint32_t smn[kThreads / kWave], smx[kThreads / kWave];
+  if (lane_id() == 0) {
+    smn[wave_id()] = mn;
+    smx[wave_id()] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / kWave; w++) {
+      mn = min(mn, smn[w]);
+      mx = max(mx, smx[w]);
+    }
+    ext[2 * f] = mn;
+    ext[2 * f + 1] = mx;
   }
 }
 
@@ -307,20 +342,37 @@ __global__ __launch_bounds__(kThreads) void k_slot_syms(FieldPtrs x, int F, uint
 
 // LCP-T: the frame's codes on the reference grid, in the reference's slot order,
 // minus the reference codes (zigzag); the new codes become the next reference.
+// The frame must stay inside the grid's float32 margin (|x| + 2 eb < 2^E) and
+// code range (|2q+1| < 2^24); a particle outside it flags the frame.
 __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64_t n, GridDev g,
                                                       const uint32_t* perm_ref,
                                                       const int32_t* q_ref, uint32_t* v_res,
-                                                      int32_t* q_new) {
+                                                      int32_t* q_new, uint32_t* err) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint32_t bad = 0;
   for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
     uint32_t i = perm_ref[s];
     for (int f = 0; f < F; f++) {
-      int64_t q = quantise(x.p[f][i], g.m[f], g.inv[f]);
+      float xv = x.p[f][i];
+      if (!__builtin_isfinite(xv)) bad |= kErrNonFinite;
+      else if (!(fabs((double)xv) + g.eb2[f] < g.lim[f])) bad |= kErrRange;
+      int64_t q = quantise(xv, g.m[f], g.inv[f]);
+      if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
+        bad |= kErrRange;
+        q = 0;
+      }
       int64_t r = q - (int64_t)q_ref[(uint64_t)f * n + s];
       v_res[(uint64_t)f * n + s] = (uint32_t)zigzag64(r);
       q_new[(uint64_t)f * n + s] = (int32_t)q;
     }
   }
+  bad |= (uint32_t)__shfl_xor((int)bad, 1, kWave);
+  bad |= (uint32_t)__shfl_xor((int)bad, 2, kWave);
+  bad |= (uint32_t)__shfl_xor((int)bad, 4, kWave);
+  bad |= (uint32_t)__shfl_xor((int)bad, 8, kWave);
+  bad |= (uint32_t)__shfl_xor((int)bad, 16, kWave);
+  bad |= (uint32_t)__shfl_xor((int)bad, 32, kWave);
+  if (lane_id() == 0 && bad) atomicOr(err, bad);
 }
 
 // ------------------------------------------------------------------ decode side
@@ -355,10 +407,9 @@ __global__ __launch_bounds__(kThreads) void k_s_blocks(const uint64_t* ids,
 }
 
 __global__ __launch_bounds__(kThreads) void k_s_recon(const uint32_t* blk, const uint32_t* corner,
-                                                      uint64_t B, const uint32_t* rel,
-                                                      const uint32_t* sup, int F, uint64_t n,
-                                                      int k, GridDev g, OutPtrs out,
-                                                      int32_t* q_slot, uint32_t* err) {
+                                                      uint64_t B, int F, uint64_t n, int k,
+                                                      GridDev g, OutPtrs out, int32_t* q_slot,
+                                                      uint32_t* err) {
   const uint32_t pm = (1u << k) - 1u;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
@@ -368,9 +419,10 @@ __global__ __launch_bounds__(kThreads) void k_s_recon(const uint32_t* blk, const
       continue;
     }
     for (int f = 0; f < F; f++) {
+      uint32_t* cell = reinterpret_cast<uint32_t*>(out.p[f]) + s;
       uint64_t q;
-      if (f < 3) q = (uint64_t)corner[(uint64_t)f * B + b] + (rel[(uint64_t)f * n + s] & pm);
-      else q = sup[(uint64_t)(f - 3) * n + s];
+      if (f < 3) q = (uint64_t)corner[(uint64_t)f * B + b] + (*cell & pm);
+      else q = *cell;
       if (q >= (uint64_t)kQLimit) {
         atomicOr(err, kErrCorrupt);
         q = 0;
@@ -381,14 +433,15 @@ __global__ __launch_bounds__(kThreads) void k_s_recon(const uint32_t* blk, const
   }
 }
 
-// LCP-T decode: q = q_ref + residual (residuals decoded as int32).
-__global__ __launch_bounds__(kThreads) void k_t_recon(const uint32_t* res, const int32_t* q_ref,
-                                                      int F, uint64_t n, GridDev g, OutPtrs out,
-                                                      int32_t* q_slot, uint32_t* err) {
+// LCP-T decode: q = q_ref + residual (residuals decoded as int32 in place).
+__global__ __launch_bounds__(kThreads) void k_t_recon(const int32_t* q_ref, int F, uint64_t n,
+                                                      GridDev g, OutPtrs out, int32_t* q_slot,
+                                                      uint32_t* err) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
     for (int f = 0; f < F; f++) {
-      int64_t q = (int64_t)q_ref[(uint64_t)f * n + s] + (int64_t)(int32_t)res[(uint64_t)f * n + s];
+      const int32_t r = reinterpret_cast<const int32_t*>(out.p[f])[s];
+      int64_t q = (int64_t)q_ref[(uint64_t)f * n + s] + (int64_t)r;
       if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
         atomicOr(err, kErrCorrupt);
         q = 0;
@@ -397,6 +450,16 @@ __global__ __launch_bounds__(kThreads) void k_t_recon(const uint32_t* res, const
       if (q_slot) q_slot[(uint64_t)f * n + s] = (int32_t)q;
     }
   }
+}
+
+// Copies the first min(size, stage) bytes (whole words) of every record into a
+// staging array, one workgroup per record.
+__global__ void k_gather_headers(const uint64_t* tab, int stage, uint8_t* dst) {
+  const uint32_t* src = reinterpret_cast<const uint32_t*>((uintptr_t)tab[2 * blockIdx.x]);
+  const uint64_t size = tab[2 * blockIdx.x + 1];
+  const uint64_t words = (size < (uint64_t)stage ? size : (uint64_t)stage) / 4;
+  uint32_t* d = reinterpret_cast<uint32_t*>(dst + (uint64_t)stage * blockIdx.x);
+  for (uint64_t w = threadIdx.x; w < words; w += blockDim.x) d[w] = src[w];
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
@@ -413,12 +476,12 @@ __global__ void k_copy_u32(const uint32_t* src, uint32_t* dst, uint64_t n) {
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-void launch_extent(const FieldPtrs& x, int F, uint64_t n, uint32_t* ext, uint32_t* err,
-                   hipStream_t s) {
-  k_extent_init<<<1, 64, 0, s>>>(ext, F, err);
-  dim3 grid(grid_for(n / 4 + 1, kThreads * 4, 1024), F);
+void launch_extent(const FieldPtrs& x, int F, uint64_t n, uint32_t* ext, uint32_t* part,
+                   uint32_t* err, hipStream_t s) {
+  uint32_t nb = grid_for(n / 4 + 1, kThreads * 4, kExtBlocks);
   LCP_TIMED("extent", (uint64_t)F * n * 4, s,
-            k_extent<<<grid, kThreads, 0, s>>>(x, n, ext, err));
+            k_extent<<<dim3(nb, F), kThreads, 0, s>>>(x, n, part, err));
+  k_extent_final<<<F, kThreads, 0, s>>>(part, (int)nb, ext);
 }
 
 void launch_quant_key(const FieldPtrs& x, uint64_t n, const GridDev& g, int k, uint64_t bn0,
@@ -500,10 +563,10 @@ void launch_slot_syms(const FieldPtrs& x, int F, uint64_t n, const GridDev& g, i
 
 void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
                     const uint32_t* perm_ref, const int32_t* q_ref, uint32_t* v_res,
-                    int32_t* q_new, hipStream_t s) {
+                    int32_t* q_new, uint32_t* err, hipStream_t s) {
   LCP_TIMED("t_resid", n * (4 + 16ull * F), s,
             k_t_resid<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(
-                x, F, n, g, perm_ref, q_ref, v_res, q_new));
+                x, F, n, g, perm_ref, q_ref, v_res, q_new, err));
 }
 
 void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, uint64_t B,
@@ -513,21 +576,23 @@ void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, ui
       ids, cnt, cum, B, n, total_blocks, bn[0], bn[1], k, corner, mark, err);
 }
 
-void launch_s_recon(const uint32_t* blk, const uint32_t* corner, uint64_t B,
-                    const uint32_t* rel, const uint32_t* sup, int F, uint64_t n, int k,
-                    const GridDev& g, const OutPtrs& out, int32_t* q_slot, uint32_t* err,
+void launch_s_recon(const uint32_t* blk, const uint32_t* corner, uint64_t B, int F, uint64_t n,
+                    int k, const GridDev& g, const OutPtrs& out, int32_t* q_slot, uint32_t* err,
                     hipStream_t s) {
-  LCP_TIMED("s_recon", n * (4 + 12 + 4ull * (F - 3) + 4ull * F + (q_slot ? 4ull * F : 0)), s,
+  LCP_TIMED("s_recon", n * (4 + 12 + 8ull * F + (q_slot ? 4ull * F : 0)), s,
             k_s_recon<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(
-                blk, corner, B, rel, sup, F, n, k, g, out, q_slot, err));
+                blk, corner, B, F, n, k, g, out, q_slot, err));
 }
 
-void launch_t_recon(const uint32_t* res, const int32_t* q_ref, int F, uint64_t n,
-                    const GridDev& g, const OutPtrs& out, int32_t* q_slot, uint32_t* err,
-                    hipStream_t s) {
-  LCP_TIMED("t_recon", n * 16ull * F, s,
+void launch_t_recon(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,
+                    const OutPtrs& out, int32_t* q_slot, uint32_t* err, hipStream_t s) {
+  LCP_TIMED("t_recon", n * (12ull * F + (q_slot ? 4ull * F : 0)), s,
             k_t_recon<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(
-                res, q_ref, F, n, g, out, q_slot, err));
+                q_ref, F, n, g, out, q_slot, err));
+}
+
+void launch_gather_headers(const uint64_t* tab, int nrec, int stage, uint8_t* dst, hipStream_t s) {
+  if (nrec) k_gather_headers<<<nrec, 128, 0, s>>>(tab, stage, dst);
 }
 
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {

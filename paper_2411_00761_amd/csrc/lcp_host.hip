@@ -88,12 +88,19 @@ struct lcp_plan_s {
   uint64_t rec_tmp_cap;
   uint32_t* host_small;  // pinned mirror of `small`
   unsigned long long* host_size;
+  uint32_t* ext_part;    // extent partials
+  // batched decode staging (pinned host + device mirrors)
+  uint8_t *hdr_host, *hdr_dev;
+  uint64_t *blobtab_host, *blobtab_dev;
+  DecArr *arrtab_host, *arrtab_dev;
+  uint32_t *prefix_host, *prefix_dev;
 
   // resident stream state
   int32_t* qpool[4] = {nullptr, nullptr, nullptr, nullptr};
   uint32_t* ppool[3] = {nullptr, nullptr, nullptr};
   int32_t* dqpool[3] = {nullptr, nullptr, nullptr};
   RefState prev, anchor, dprev, danchor;
+  RefState sr_state_tmp;  // reference state of the spatial candidate of the current frame
   bool have_eb = false;
   double eb_f[kMaxF];
   uint64_t seq = 0;
@@ -191,7 +198,8 @@ lcp_status extent(lcp_plan_s* P, const float* const* x, uint64_t n, float* lo, f
   FieldPtrs fp;
   memset(&fp, 0, sizeof(fp));
   for (int f = 0; f < P->F; f++) fp.p[f] = x[f];
-  launch_extent(fp, P->F, n, P->small + 2, P->small + 1, s);
+  launch_fill_u32(P->small + 1, 1, 0u, s);
+  launch_extent(fp, P->F, n, P->small + 2, P->ext_part, P->small + 1, s);
   HIP_OK(hipMemcpyAsync(P->host_small, P->small, sizeof(uint32_t) * (2 + 2 * P->F),
                         hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
@@ -228,7 +236,7 @@ lcp_status field_eb(const lcp_params& p, int F, const float* lo, const float* hi
 }
 
 // ------------------------------------------------------------------ encode driver
-lcp_status finish_record(lcp_plan_s* P, uint64_t* size, hipStream_t s) {
+lcp_status finish_record(lcp_plan_s* P, uint64_t* size, uint32_t* flags, hipStream_t s) {
   HIP_OK(hipMemcpyAsync(P->host_size, P->size_dev, sizeof(unsigned long long),
                         hipMemcpyDeviceToHost, s));
   HIP_OK(hipMemcpyAsync(P->host_small + 1, P->small + 1, sizeof(uint32_t),
@@ -236,6 +244,7 @@ lcp_status finish_record(lcp_plan_s* P, uint64_t* size, hipStream_t s) {
   HIP_OK(hipStreamSynchronize(s));
   if (g_timer_plan == P) timer_collect(P);
   *size = *P->host_size;
+  if (flags) *flags = P->host_small[1];
   if (P->host_small[1] & kErrCapacity) return LCP_ERR_CAPACITY;
   return LCP_OK;
 }
@@ -307,26 +316,27 @@ lcp_status compress_s(lcp_plan_s* P, const float* const* x, uint64_t n, const Ho
   launch_encode(set, n, P->chunk_log2, P->work, P->chunk_words, P->max_chunks, h, B_dev, out,
                 cap, P->size_dev, P->small + 1, s);
   res->perm = perm;
-  return finish_record(P, &res->size, s);
+  return finish_record(P, &res->size, nullptr, s);
 }
 
-// LCP-T on one frame against a resident reference.
+// LCP-T on one frame against a resident reference.  Whether the frame fits the
+// reference grid (finite values, float32 margin, code range) is checked by the
+// residual kernel itself, so no extent pass is needed.
 lcp_status compress_t(lcp_plan_s* P, const float* const* x, uint64_t n, const RefState& ref,
-                      const float* lo, const float* hi, uint64_t seq, uint8_t* out,
-                      uint64_t cap, int32_t* q_new, uint64_t* size, hipStream_t s) {
+                      uint64_t seq, uint8_t* out, uint64_t cap, int32_t* q_new, uint64_t* size,
+                      hipStream_t s) {
   const int F = P->F;
-  for (int f = 0; f < F; f++) {
-    const HostGrid& g = ref.grid[f];
-    double M = fmax(fabs((double)lo[f]), fabs((double)hi[f])) + 2.0 * g.eb;
-    if (!(M < ldexp(1.0, g.E))) return LCP_ERR_RANGE;
-    if (host_quant(lo[f], g) < -(int64_t)kQLimit) return LCP_ERR_RANGE;
-    if (host_quant(hi[f], g) >= (int64_t)kQLimit) return LCP_ERR_RANGE;
-  }
   FieldPtrs fp;
   memset(&fp, 0, sizeof(fp));
   for (int f = 0; f < F; f++) fp.p[f] = x[f];
   GridDev gd = to_dev(ref.grid, F);
-  launch_t_resid(fp, F, n, gd, P->ppool[ref.perm], P->qpool[ref.q], P->v_slot, q_new, s);
+  for (int f = 0; f < F; f++) {
+    gd.eb2[f] = 2.0 * ref.grid[f].eb;
+    gd.lim[f] = ldexp(1.0, ref.grid[f].E);
+  }
+  launch_fill_u32(P->small + 1, 1, 0u, s);
+  launch_t_resid(fp, F, n, gd, P->ppool[ref.perm], P->qpool[ref.q], P->v_slot, q_new,
+                 P->small + 1, s);
   ArrSet set;
   memset(&set, 0, sizeof(set));
   set.A = F;
@@ -345,10 +355,13 @@ lcp_status compress_t(lcp_plan_s* P, const float* const* x, uint64_t n, const Re
     h.m[f] = ref.grid[f].m;
     h.eb_q[f] = ref.grid[f].eb_q;
   }
-  HIP_OK(hipMemsetAsync(P->small + 1, 0, sizeof(uint32_t), s));
   launch_encode(set, n, P->chunk_log2, P->work, P->chunk_words, P->max_chunks, h, P->small,
                 out, cap, P->size_dev, P->small + 1, s);
-  return finish_record(P, size, s);
+  uint32_t flags = 0;
+  lcp_status st = finish_record(P, size, &flags, s);
+  if (flags & kErrNonFinite) return LCP_ERR_ARG;
+  if (flags & kErrRange) return LCP_ERR_RANGE;
+  return st;
 }
 
 // ------------------------------------------------------------------ LCP-FSM
@@ -409,6 +422,7 @@ int free_perm(const lcp_plan_s* P) {
 }
 
 // One frame through Alg. 1 + LCP-FSM (or plain LCP-S for single-frame plans).
+// The extent pass and the spatial grid are computed only when LCP-S runs.
 lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, uint64_t cap,
                           uint64_t* size, int* used, uint32_t* perm_out, hipStream_t s) {
   const int F = P->F;
@@ -416,32 +430,22 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
   if (n == 0 || n > P->N || fr.method < 0 || fr.method > 2) return LCP_ERR_ARG;
   for (int f = 0; f < F; f++)
     if (!fr.fields[f]) return LCP_ERR_ARG;
-  float lo[kMaxF], hi[kMaxF];
-  lcp_status st = extent(P, fr.fields, n, lo, hi, s);
-  if (st) return st;
-  double eb_f[kMaxF];
-  if (P->p.multi_frame && P->have_eb) memcpy(eb_f, P->eb_f, sizeof(eb_f));
-  else if ((st = field_eb(P->p, F, lo, hi, eb_f))) return st;
-  HostGrid sg[kMaxF];
-  for (int f = 0; f < F; f++)
-    if ((st = make_grid(lo[f], hi[f], eb_f[f], &sg[f]))) return st;
-
+  const bool multi = P->p.multi_frame != 0;
   const RefState* ref = reference_for(P, n);
   int decision;
   if (fr.method == LCP_METHOD_S) decision = LCP_DECIDE_S;
   else if (fr.method == LCP_METHOD_T) decision = LCP_DECIDE_T;
   else decision = fsm_decide(P, ref != nullptr);
   if (decision != LCP_DECIDE_S && !ref) return LCP_ERR_NO_REFERENCE;
-  if (fr.method == LCP_METHOD_T && !P->p.multi_frame) return LCP_ERR_ARG;
 
-  const bool multi = P->p.multi_frame != 0;
+  lcp_status st = LCP_OK;
   int qt_i = -1, qs_i = -1, ps_i = -1;
   uint64_t size_s = 0, size_t_ = 0;
   bool have_s = false, have_t = false;
   if (decision != LCP_DECIDE_S) {
     qt_i = free_q(P, -1);
-    st = compress_t(P, fr.fields, n, *ref, lo, hi, P->seq, P->rec_tmp, P->rec_tmp_cap,
-                    P->qpool[qt_i], &size_t_, s);
+    st = compress_t(P, fr.fields, n, *ref, P->seq, P->rec_tmp, P->rec_tmp_cap, P->qpool[qt_i],
+                    &size_t_, s);
     if (st == LCP_OK) have_t = true;
     else if (st == LCP_ERR_RANGE && fr.method != LCP_METHOD_T) st = LCP_OK;  // T infeasible
     else return st;
@@ -449,7 +453,15 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
   bool need_s = decision != LCP_DECIDE_T || !have_t ||
                 (fr.method == LCP_METHOD_AUTO && (!P->have_last_s || size_t_ > P->last_s));
   SResult sr;
+  double eb_f[kMaxF];
   if (need_s) {
+    float lo[kMaxF], hi[kMaxF];
+    if ((st = extent(P, fr.fields, n, lo, hi, s))) return st;
+    if (multi && P->have_eb) memcpy(eb_f, P->eb_f, sizeof(eb_f));
+    else if ((st = field_eb(P->p, F, lo, hi, eb_f))) return st;
+    HostGrid sg[kMaxF];
+    for (int f = 0; f < F; f++)
+      if ((st = make_grid(lo[f], hi[f], eb_f[f], &sg[f]))) return st;
     if (multi) {
       qs_i = free_q(P, qt_i);
       ps_i = free_perm(P);
@@ -457,13 +469,23 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
     st = compress_s(P, fr.fields, n, sg, hi, P->k, P->seq, out, cap,
                     multi ? P->qpool[qs_i] : nullptr, &sr, s);
     if (st == LCP_ERR_CAPACITY && have_t && size_t_ < sr.size) {
-      st = LCP_OK;  // the T record may still fit
+      st = LCP_OK;  // the temporal record is the smaller one and may still fit
     } else if (st) {
       if (st == LCP_ERR_CAPACITY) *size = sr.size;
       return st;
     } else {
       have_s = true;
       size_s = sr.size;
+      if (multi) {
+        RefState r;
+        r.valid = true;
+        r.seq = P->seq;
+        r.n = n;
+        memcpy(r.grid, sg, sizeof(sg));
+        r.q = qs_i;
+        r.perm = ps_i;
+        P->sr_state_tmp = r;
+      }
     }
   }
   const bool chose_t = have_t && (!have_s || size_t_ < size_s);
@@ -484,29 +506,21 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
     // Alg. 1 bookkeeping: the previous frame; anchors are first-in-batch S frames
     if (!chose_t) {
       launch_copy_perm(sr.perm, P->ppool[ps_i], n, s);
-      RefState r;
-      r.valid = true;
-      r.seq = P->seq;
-      r.n = n;
-      memcpy(r.grid, sg, sizeof(sg));
-      r.q = qs_i;
-      r.perm = ps_i;
-      P->prev = r;
-      if (first_in_batch(P, P->seq)) P->anchor = r;
+      P->prev = P->sr_state_tmp;
+      if (first_in_batch(P, P->seq)) P->anchor = P->sr_state_tmp;
     } else {
       RefState r = *ref;  // a T frame keeps its reference's grid and slot order
       r.seq = P->seq;
       r.q = qt_i;
       P->prev = r;
     }
-    if (!P->have_eb) {
-      memcpy(P->eb_f, eb_f, sizeof(eb_f));
+    if (!P->have_eb && have_s) {
+      memcpy(P->eb_f, eb_f, sizeof(eb_f));  // the first frame is always spatial
       P->have_eb = true;
     }
   }
   if (perm_out) {
-    const uint32_t* src = chose_t ? P->ppool[ref->perm] : sr.perm;
-    if (!chose_t && multi) src = P->ppool[ps_i];
+    const uint32_t* src = chose_t ? P->ppool[P->prev.perm] : (multi ? P->ppool[ps_i] : sr.perm);
     launch_copy_perm(src, perm_out, n, s);
   }
   P->seq++;
@@ -591,131 +605,195 @@ lcp_status parse_header(const uint8_t* b, uint64_t size, ParsedHdr* h) {
   return LCP_OK;
 }
 
-lcp_status read_err(lcp_plan_s* P, hipStream_t s) {
+constexpr int kMaxBatchFrames = 64;
+constexpr int kHdrStage = 512;  // header bytes staged per record
+constexpr int kMaxBatchArrays = kMaxBatchFrames * kMaxF + 2;
+
+// Decode one group of arrays (descriptors staged at arrtab_host[base..base+A))
+// through the batched kernels; the LUT slots start at array `base`.
+lcp_status decode_arrays(lcp_plan_s* P, int base, int A, int cl, uint64_t bytes, hipStream_t s) {
+  uint32_t* hp = P->prefix_host + 2 * base;
+  uint32_t* fp = hp + A;
+  uint32_t hb = 0, fb = 0;
+  for (int a = 0; a < A; a++) {
+    hp[a] = hb;
+    fp[a] = fb;
+    hb += decode_blocks(P->arrtab_host[base + a], cl, true);
+    fb += decode_blocks(P->arrtab_host[base + a], cl, false);
+  }
+  HIP_OK(hipMemcpyAsync(P->arrtab_dev + base, P->arrtab_host + base, sizeof(DecArr) * A,
+                        hipMemcpyHostToDevice, s));
+  HIP_OK(hipMemcpyAsync(P->prefix_dev + 2 * base, hp, sizeof(uint32_t) * 2 * A,
+                        hipMemcpyHostToDevice, s));
+  launch_decode(P->arrtab_dev + base, A, P->prefix_dev + 2 * base, hb,
+                P->prefix_dev + 2 * base + A, fb, cl, bytes, P->lut + ((uint64_t)base << kMaxLen),
+                P->small + 1, s);
+  return LCP_OK;
+}
+
+// Decompress up to kMaxBatchFrames records: headers in one gather + copy, the
+// entropy decoding of every position / residual array in one set of launches,
+// then the per-frame reconstruction in stream order (temporal frames need the
+// codes of their reference).  Stream state is committed only on success.
+lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
+                            const lcp_frame_out* outs, uint64_t* n_out, hipStream_t s) {
+  const int F = P->F;
+  const bool multi = P->p.multi_frame != 0;
+  for (uint64_t j = 0; j < nf; j++) {
+    if (!blobs[j].data || ((uintptr_t)blobs[j].data & 3)) return LCP_ERR_ARG;
+    P->blobtab_host[2 * j] = (uint64_t)(uintptr_t)blobs[j].data;
+    P->blobtab_host[2 * j + 1] = blobs[j].size;
+  }
+  HIP_OK(hipMemcpyAsync(P->blobtab_dev, P->blobtab_host, 16 * nf, hipMemcpyHostToDevice, s));
+  launch_gather_headers(P->blobtab_dev, (int)nf, kHdrStage, P->hdr_dev, s);
+  HIP_OK(hipMemcpyAsync(P->hdr_host, P->hdr_dev, (size_t)kHdrStage * nf, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+
+  std::vector<ParsedHdr> H(nf);
+  std::vector<int> refq(nf, -1), dq(nf, -1);
+  RefState sp = P->dprev, sa = P->danchor;
+  for (uint64_t j = 0; j < nf; j++) {
+    lcp_status st = parse_header(P->hdr_host + (size_t)kHdrStage * j, blobs[j].size, &H[j]);
+    if (st) return st;
+    const ParsedHdr& h = H[j];
+    if (h.F != F || h.cl > 12 || h.n > P->N) return LCP_ERR_ARG;
+    n_out[j] = h.n;
+    if (h.n > outs[j].capacity) return LCP_ERR_CAPACITY;
+    for (int f = 0; f < F; f++)
+      if (!outs[j].fields[f]) return LCP_ERR_ARG;
+    if (h.mode == 1) {
+      if (sp.valid && sp.seq == h.ref_seq && sp.n == h.n) refq[j] = sp.q;
+      else if (sa.valid && sa.seq == h.ref_seq && sa.n == h.n) refq[j] = sa.q;
+      else return LCP_ERR_NO_REFERENCE;
+    }
+    if (multi) {
+      for (int i = 0; i < 3; i++)
+        if (!(sp.valid && sp.q == i) && !(sa.valid && sa.q == i)) {
+          dq[j] = i;
+          break;
+        }
+      RefState r;
+      r.valid = true;
+      r.seq = h.seq;
+      r.n = h.n;
+      r.q = dq[j];
+      sp = r;
+      if (h.mode == 0 && first_in_batch(P, h.seq)) sa = r;
+    }
+  }
+  // ---- entropy decoding of every array that lands in the output buffers
+  launch_fill_u32(P->small + 1, 1, 0u, s);
+  int A = 0;
+  uint64_t bytes = 0;
+  int cl = nf ? H[0].cl : 10;
+  bool same_cl = true;
+  for (uint64_t j = 0; j < nf; j++) same_cl &= H[j].cl == cl;
+  for (uint64_t j = 0; j < nf && same_cl; j++) {
+    const ParsedHdr& h = H[j];
+    const uint8_t* rec = reinterpret_cast<const uint8_t*>(blobs[j].data);
+    for (int a = (h.mode == 0 ? 2 : 0); a < h.A; a++) {
+      const int f = h.mode == 0 ? a - 2 : a;
+      DecArr& d = P->arrtab_host[A++];
+      d.data = rec + h.aoff[a];
+      d.nbytes = h.anb[a];
+      d.n = h.an[a];
+      d.coder = h.coder[a];
+      d.param = h.param[a];
+      d.used = h.used[a];
+      d.out = outs[j].fields[f];
+      d.mode = h.mode == 0 ? 2 : 3;
+      d.limit = h.mode == 0 ? (f < 3 ? (1ull << h.k) : (uint64_t)kQLimit) : (1ull << 25);
+      bytes += h.anb[a] + 4 * h.an[a];
+    }
+  }
+  if (same_cl) {
+    lcp_status st = decode_arrays(P, 0, A, cl, bytes, s);
+    if (st) return st;
+  }
+  // ---- reconstruction in stream order
+  int extra = A;  // staging slots for the id / count arrays of spatial frames
+  for (uint64_t j = 0; j < nf; j++) {
+    const ParsedHdr& h = H[j];
+    const uint64_t n = h.n;
+    const uint8_t* rec = reinterpret_cast<const uint8_t*>(blobs[j].data);
+    GridDev gd;
+    memset(&gd, 0, sizeof(gd));
+    for (int f = 0; f < F; f++) {
+      gd.m[f] = h.m[f];
+      gd.eb_q[f] = h.eb_q[f];
+    }
+    OutPtrs op;
+    memset(&op, 0, sizeof(op));
+    for (int f = 0; f < F; f++) op.p[f] = outs[j].fields[f];
+    int32_t* q_slot = multi ? P->dqpool[dq[j]] : nullptr;
+    // staging slots: at most kMaxF + 2 per frame beyond the batched arrays
+    if (extra + kMaxF + 2 > kMaxBatchArrays + 2 * kMaxBatchFrames) return LCP_ERR_ARG;
+    if (!same_cl) {  // mixed chunk sizes: decode this frame's arrays on their own
+      int a0 = extra;
+      for (int a = (h.mode == 0 ? 2 : 0); a < h.A; a++) {
+        const int f = h.mode == 0 ? a - 2 : a;
+        DecArr& d = P->arrtab_host[extra++];
+        d.data = rec + h.aoff[a];
+        d.nbytes = h.anb[a];
+        d.n = h.an[a];
+        d.coder = h.coder[a];
+        d.param = h.param[a];
+        d.used = h.used[a];
+        d.out = outs[j].fields[f];
+        d.mode = h.mode == 0 ? 2 : 3;
+        d.limit = h.mode == 0 ? (f < 3 ? (1ull << h.k) : (uint64_t)kQLimit) : (1ull << 25);
+      }
+      lcp_status st = decode_arrays(P, a0, extra - a0, h.cl, 0, s);
+      if (st) return st;
+    }
+    if (h.mode == 0) {
+      const uint64_t B = h.B;
+      unsigned __int128 tot = (unsigned __int128)h.bn[0] * h.bn[1] * h.bn[2];
+      if (h.bn[0] == 0 || h.bn[1] == 0 || h.bn[2] == 0 || tot >= ((unsigned __int128)1 << 63))
+        return LCP_ERR_CORRUPT;
+      const uint64_t total_blocks = (uint64_t)tot;
+      for (int a = 0; a < 2; a++) {
+        DecArr& d = P->arrtab_host[extra + a];
+        d.data = rec + h.aoff[a];
+        d.nbytes = h.anb[a];
+        d.n = h.an[a];
+        d.coder = h.coder[a];
+        d.param = h.param[a];
+        d.used = h.used[a];
+        d.out = a == 0 ? (void*)P->v_id : (void*)P->v_cnt;
+        d.mode = a;  // ids raw, counts unzigzagged
+        d.limit = a == 0 ? total_blocks : ~0ull;
+      }
+      lcp_status st = decode_arrays(P, extra, 2, h.cl, 0, s);
+      if (st) return st;
+      extra += 2;
+      uint64_t* ids = P->v_id;
+      uint64_t* cnt = P->v_cnt;
+      uint64_t* cum = P->ids;
+      scan_device<uint64_t>(ids, B, nullptr, false, P->scan_tmp, s);
+      scan_device<uint64_t>(cnt, B, nullptr, false, P->scan_tmp, s);
+      HIP_OK(hipMemcpyAsync(cum, cnt, B * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+      scan_device<uint64_t>(cum, B, nullptr, false, P->scan_tmp, s);
+      launch_fill_u32(P->flags, n, 0u, s);
+      launch_s_blocks(ids, cnt, cum, B, n, total_blocks, h.bn, h.k, P->corner, P->flags,
+                      P->small + 1, s);
+      uint32_t* tmp32 = reinterpret_cast<uint32_t*>(P->scan_tmp);
+      scan_device<uint32_t>(P->flags, n, nullptr, false, tmp32, s);
+      for (int d = 0; d < 3; d++)
+        scan_device<uint32_t>(reinterpret_cast<uint32_t*>(outs[j].fields[d]), n, nullptr, false,
+                              tmp32, s);
+      launch_s_recon(P->flags, P->corner, B, F, n, h.k, gd, op, q_slot, P->small + 1, s);
+    } else {
+      launch_t_recon(P->dqpool[refq[j]], F, n, gd, op, q_slot, P->small + 1, s);
+    }
+  }
   HIP_OK(hipMemcpyAsync(P->host_small + 1, P->small + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
   if (g_timer_plan == P) timer_collect(P);
-  return (P->host_small[1] & kErrCorrupt) ? LCP_ERR_CORRUPT : LCP_OK;
-}
-
-lcp_status decompress_frame(lcp_plan_s* P, const lcp_blob& blob, const lcp_frame_out& o,
-                            uint64_t* n_out, hipStream_t s) {
-  const int F = P->F;
-  if (!blob.data || ((uintptr_t)blob.data & 3)) return LCP_ERR_ARG;
-  uint8_t hb[kHdrBytes + 8 * kMaxF + kDirBytes * kMaxArrays];
-  uint64_t want = blob.size < sizeof(hb) ? blob.size : sizeof(hb);
-  if (want < (uint64_t)kHdrBytes) return LCP_ERR_CORRUPT;
-  HIP_OK(hipMemcpyAsync(hb, blob.data, want, hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  ParsedHdr h;
-  lcp_status st = parse_header(hb, blob.size, &h);
-  if (st) return st;
-  if (h.F != F || h.cl > 12) return LCP_ERR_ARG;
-  const uint64_t n = h.n;
-  *n_out = n;
-  if (n > P->N) return LCP_ERR_ARG;
-  if (n > o.capacity) return LCP_ERR_CAPACITY;
-  for (int f = 0; f < F; f++)
-    if (!o.fields[f]) return LCP_ERR_ARG;
-  const RefState* ref = nullptr;
-  if (h.mode == 1) {
-    if (P->dprev.valid && P->dprev.seq == h.ref_seq && P->dprev.n == n) ref = &P->dprev;
-    else if (P->danchor.valid && P->danchor.seq == h.ref_seq && P->danchor.n == n) ref = &P->danchor;
-    if (!ref) return LCP_ERR_NO_REFERENCE;
-  }
-  const bool multi = P->p.multi_frame != 0;
-  int dq = -1;
+  if (P->host_small[1] & kErrCorrupt) return LCP_ERR_CORRUPT;
   if (multi) {
-    for (int i = 0; i < 3; i++)
-      if (!(P->dprev.valid && P->dprev.q == i) && !(P->danchor.valid && P->danchor.q == i)) {
-        dq = i;
-        break;
-      }
-  }
-  int32_t* q_slot = multi ? P->dqpool[dq] : nullptr;
-  const uint8_t* rec = reinterpret_cast<const uint8_t*>(blob.data);
-  HIP_OK(hipMemsetAsync(P->small + 1, 0, sizeof(uint32_t), s));
-  DecSet ds;
-  memset(&ds, 0, sizeof(ds));
-  ds.A = h.A;
-  ds.chunk_log2 = h.cl;
-  GridDev gd;
-  memset(&gd, 0, sizeof(gd));
-  for (int f = 0; f < F; f++) {
-    gd.m[f] = h.m[f];
-    gd.eb_q[f] = h.eb_q[f];
-  }
-  OutPtrs op;
-  memset(&op, 0, sizeof(op));
-  for (int f = 0; f < F; f++) op.p[f] = o.fields[f];
-  for (int a = 0; a < h.A; a++) {
-    DecArr& d = ds.a[a];
-    d.data = rec + h.aoff[a];
-    d.nbytes = h.anb[a];
-    d.n = h.an[a];
-    d.coder = h.coder[a];
-    d.param = h.param[a];
-    d.used = h.used[a];
-  }
-  if (h.mode == 0) {
-    const uint64_t B = h.B;
-    unsigned __int128 tot = (unsigned __int128)h.bn[0] * h.bn[1] * h.bn[2];
-    if (h.bn[0] == 0 || h.bn[1] == 0 || h.bn[2] == 0 || tot >= ((unsigned __int128)1 << 63))
-      return LCP_ERR_CORRUPT;
-    const uint64_t total_blocks = (uint64_t)tot;
-    uint64_t* ids = P->v_id;   // deltas -> ids
-    uint64_t* cnt = P->v_cnt;  // count deltas -> counts
-    uint64_t* cum = P->ids;    // running counts
-    uint32_t* rel = P->v_slot;
-    ds.a[0].out = ids;
-    ds.a[0].mode = 0;
-    ds.a[0].limit = total_blocks;
-    ds.a[1].out = cnt;
-    ds.a[1].mode = 1;
-    ds.a[1].limit = ~0ull;
-    for (int d = 0; d < 3; d++) {
-      ds.a[2 + d].out = rel + (uint64_t)d * n;
-      ds.a[2 + d].mode = 2;
-      ds.a[2 + d].limit = 1ull << h.k;
-    }
-    for (int f = 3; f < F; f++) {
-      ds.a[2 + f].out = rel + (uint64_t)f * n;
-      ds.a[2 + f].mode = 2;
-      ds.a[2 + f].limit = (uint64_t)kQLimit;
-    }
-    launch_decode(ds, n, P->max_chunks, P->lut, P->small + 1, s);
-    scan_device<uint64_t>(ids, B, nullptr, false, P->scan_tmp, s);
-    scan_device<uint64_t>(cnt, B, nullptr, false, P->scan_tmp, s);
-    HIP_OK(hipMemcpyAsync(cum, cnt, B * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-    scan_device<uint64_t>(cum, B, nullptr, false, P->scan_tmp, s);
-    launch_fill_u32(P->flags, n, 0u, s);
-    launch_s_blocks(ids, cnt, cum, B, n, total_blocks, h.bn, h.k, P->corner, P->flags,
-                    P->small + 1, s);
-    scan_device<uint32_t>(P->flags, n, nullptr, false, reinterpret_cast<uint32_t*>(P->scan_tmp), s);
-    for (int d = 0; d < 3; d++)
-      scan_device<uint32_t>(rel + (uint64_t)d * n, n, nullptr, false,
-                            reinterpret_cast<uint32_t*>(P->scan_tmp), s);
-    launch_s_recon(P->flags, P->corner, B, rel, rel + 3 * n, F, n, h.k, gd, op, q_slot,
-                   P->small + 1, s);
-  } else {
-    for (int f = 0; f < F; f++) {
-      ds.a[f].out = P->v_slot + (uint64_t)f * n;
-      ds.a[f].mode = 3;
-      ds.a[f].limit = 1ull << 25;
-    }
-    launch_decode(ds, n, P->max_chunks, P->lut, P->small + 1, s);
-    launch_t_recon(P->v_slot, P->dqpool[ref->q], F, n, gd, op, q_slot, P->small + 1, s);
-  }
-  st = read_err(P, s);
-  if (st) return st;
-  if (multi) {
-    RefState r;
-    r.valid = true;
-    r.seq = h.seq;
-    r.n = n;
-    r.q = dq;
-    P->dprev = r;
-    if (h.mode == 0 && first_in_batch(P, h.seq)) P->danchor = r;
+    P->dprev = sp;
+    P->danchor = sa;
   }
   return LCP_OK;
 }
@@ -740,7 +818,12 @@ lcp_status alloc_plan(lcp_plan_s* P) {
   A_(P->v_slot, (uint64_t)F * N);
   P->max_chunks = (N + (1ull << P->chunk_log2) - 1) >> P->chunk_log2;
   A_(P->chunk_words, (uint64_t)kMaxArrays * P->max_chunks + 1);
-  A_(P->lut, (uint64_t)kMaxArrays << kMaxLen);
+  A_(P->lut, (uint64_t)(kMaxBatchArrays + 2 * kMaxBatchFrames) << kMaxLen);
+  A_(P->ext_part, 2 * kMaxF * 256);
+  A_(P->hdr_dev, (uint64_t)kHdrStage * kMaxBatchFrames);
+  A_(P->blobtab_dev, 2 * kMaxBatchFrames);
+  A_(P->arrtab_dev, kMaxBatchArrays + 2 * kMaxBatchFrames);
+  A_(P->prefix_dev, 2 * (kMaxBatchArrays + 2 * kMaxBatchFrames));
   A_(P->corner, 3 * N);
   uint64_t sn = N > 256 * ntiles ? N : 256 * ntiles;
   P->scan_tmp_n = scan_tmp_elems(sn);
@@ -760,6 +843,11 @@ lcp_status alloc_plan(lcp_plan_s* P) {
     return LCP_ERR_DEVICE;
   if (hipHostMalloc((void**)&P->host_size, sizeof(unsigned long long), 0) != hipSuccess)
     return LCP_ERR_DEVICE;
+  if (hipHostMalloc((void**)&P->hdr_host, (size_t)kHdrStage * kMaxBatchFrames, 0) != hipSuccess ||
+      hipHostMalloc((void**)&P->blobtab_host, 16 * kMaxBatchFrames, 0) != hipSuccess ||
+      hipHostMalloc((void**)&P->arrtab_host, sizeof(DecArr) * (kMaxBatchArrays + 2 * kMaxBatchFrames), 0) != hipSuccess ||
+      hipHostMalloc((void**)&P->prefix_host, 8 * (kMaxBatchArrays + 2 * kMaxBatchFrames), 0) != hipSuccess)
+    return LCP_ERR_DEVICE;
   return LCP_OK;
 }
 
@@ -767,6 +855,8 @@ void free_plan(lcp_plan_s* P) {
   for (void* p : P->allocs) (void)hipFree(p);
   if (P->host_small) (void)hipHostFree(P->host_small);
   if (P->host_size) (void)hipHostFree(P->host_size);
+  for (void* hp : {(void*)P->hdr_host, (void*)P->blobtab_host, (void*)P->arrtab_host, (void*)P->prefix_host})
+    if (hp) (void)hipHostFree(hp);
   for (auto e : P->ev_free) (void)hipEventDestroy(e);
   for (auto& pr : P->ev_pending) {
     (void)hipEventDestroy(pr.first);
@@ -901,6 +991,22 @@ void lcp_plan_destroy(lcp_plan_t plan) {
 
 int lcp_plan_block_log2(lcp_plan_t plan) { return plan ? plan->k : -1; }
 
+lcp_status lcp_plan_reset(lcp_plan_t plan) {
+  if (!plan) return LCP_ERR_ARG;
+  plan->prev = RefState();
+  plan->anchor = RefState();
+  plan->dprev = RefState();
+  plan->danchor = RefState();
+  plan->have_eb = false;
+  plan->seq = 0;
+  plan->fsm_t = false;
+  plan->interval = 1;
+  plan->countdown = 0;
+  plan->last_s = 0;
+  plan->have_last_s = false;
+  return LCP_OK;
+}
+
 uint64_t lcp_bound(lcp_plan_t plan, uint64_t n) { return plan ? bound_bytes(plan->F, n) : 0; }
 
 lcp_status lcp_compress(lcp_plan_t plan, uint64_t n_frames, const lcp_frame_in* frames,
@@ -935,8 +1041,9 @@ lcp_status lcp_decompress(lcp_plan_t plan, uint64_t n_frames, const lcp_blob* bl
                           const lcp_frame_out* outs, uint64_t* n_out, hipStream_t stream) {
   if (!plan || (n_frames && (!blobs || !outs || !n_out))) return LCP_ERR_ARG;
   TimerScope ts(plan);
-  for (uint64_t j = 0; j < n_frames; j++) {
-    lcp_status st = decompress_frame(plan, blobs[j], outs[j], &n_out[j], stream);
+  for (uint64_t j = 0; j < n_frames; j += kMaxBatchFrames) {
+    uint64_t g = n_frames - j < (uint64_t)kMaxBatchFrames ? n_frames - j : kMaxBatchFrames;
+    lcp_status st = decompress_group(plan, g, blobs + j, outs + j, n_out + j, stream);
     if (st) return st;
   }
   timer_collect(plan);

@@ -21,6 +21,8 @@ struct GridDev {
   float m[kMaxF];
   float eb_q[kMaxF];
   double inv[kMaxF];
+  double eb2[kMaxF];  // 2 * the user's bound (temporal feasibility check)
+  double lim[kMaxF];  // 2^E: |x| + 2 eb must stay below it on this grid
 };
 
 // One symbol array to be coded: u64 or u32 values; its length is n, or
@@ -64,17 +66,13 @@ struct DecArr {
   int mode;        // 0 u64, 1 unzigzag -> int64 in u64, 2 u32, 3 unzigzag -> int32 in u32
   uint64_t limit;  // raw values >= limit are corrupt
 };
-struct DecSet {
-  DecArr a[kMaxArrays];
-  int A;
-  int chunk_log2;
-};
 
 // Device error word bits.
 enum : uint32_t {
   kErrNonFinite = 1u,
   kErrCorrupt = 2u,
   kErrCapacity = 4u,
+  kErrRange = 8u,  // a temporal frame left its reference grid's range
 };
 
 // ---- kernel timer (lcp_host.hip) ----
@@ -92,8 +90,10 @@ void ktimer_end(hipStream_t s, uint64_t bytes);
   } while (0)
 
 // ---- kernels_core.hip ----
-void launch_extent(const FieldPtrs& x, int F, uint64_t n, uint32_t* ext, uint32_t* err,
-                   hipStream_t s);
+// Per-field extent as sortable keys ext[2f] (min), ext[2f+1] (max); part holds
+// 2 * F * 256 partials; err gets kErrNonFinite for NaN/Inf input (it is not cleared).
+void launch_extent(const FieldPtrs& x, int F, uint64_t n, uint32_t* ext, uint32_t* part,
+                   uint32_t* err, hipStream_t s);
 void launch_quant_key(const FieldPtrs& x, uint64_t n, const GridDev& g, int k, uint64_t bn0,
                       uint64_t bn1, uint64_t* keys, uint32_t* vals, hipStream_t s);
 // Stable LSD radix sort of (key, value) by the low `bits` key bits.  Returns the
@@ -111,20 +111,26 @@ void launch_block_syms(const uint64_t* ids, const uint32_t* starts, const uint32
 void launch_slot_syms(const FieldPtrs& x, int F, uint64_t n, const GridDev& g, int k,
                       const uint32_t* perm, uint32_t* v_rel, uint32_t* v_sup, int32_t* q_slot,
                       hipStream_t s);
+// LCP-T residuals; err gets kErrNonFinite / kErrRange when the frame cannot be
+// coded on the reference grid.
 void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
                     const uint32_t* perm_ref, const int32_t* q_ref, uint32_t* v_res,
-                    int32_t* q_new, hipStream_t s);
+                    int32_t* q_new, uint32_t* err, hipStream_t s);
 void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, uint64_t B,
                      uint64_t n, uint64_t total_blocks, const uint32_t* bn, int k,
                      uint32_t* corner, uint32_t* mark, uint32_t* err, hipStream_t s);
-void launch_s_recon(const uint32_t* blk, const uint32_t* corner, uint64_t B,
-                    const uint32_t* rel, const uint32_t* sup, int F, uint64_t n, int k,
-                    const GridDev& g, const OutPtrs& out, int32_t* q_slot, uint32_t* err,
+// Reconstruction in place: out.p[f] holds the decoded u32 symbols (scanned
+// relative positions for f < 3, codes for supplementary fields) and receives
+// the float32 values.
+void launch_s_recon(const uint32_t* blk, const uint32_t* corner, uint64_t B, int F, uint64_t n,
+                    int k, const GridDev& g, const OutPtrs& out, int32_t* q_slot, uint32_t* err,
                     hipStream_t s);
-void launch_t_recon(const uint32_t* res, const int32_t* q_ref, int F, uint64_t n,
-                    const GridDev& g, const OutPtrs& out, int32_t* q_slot, uint32_t* err,
-                    hipStream_t s);
+// out.p[f] holds int32 residuals; q_slot receives q_ref + residual.
+void launch_t_recon(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,
+                    const OutPtrs& out, int32_t* q_slot, uint32_t* err, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+// tab: nrec (device pointer, byte size) pairs; dst: nrec * stage bytes.
+void launch_gather_headers(const uint64_t* tab, int nrec, int stage, uint8_t* dst, hipStream_t s);
 void launch_copy_perm(const uint32_t* src, uint32_t* dst, uint64_t n, hipStream_t s);
 
 // ---- kernels_codec.hip ----
@@ -132,7 +138,13 @@ void launch_encode(const ArrSet& set, uint64_t max_n, int chunk_log2, ArrWork* w
                    uint32_t* chunk_words, uint64_t max_chunks, const RecHdr& h,
                    const uint32_t* B_dev, uint8_t* out, uint64_t cap,
                    unsigned long long* size_dev, uint32_t* err, hipStream_t s);
-void launch_decode(const DecSet& set, uint64_t max_n, uint64_t max_chunks, uint32_t* lut,
-                   uint32_t* err, hipStream_t s);
+// Workgroups needed by one array in the Huffman (huff=true) or fixed-length
+// decode launch (0 when the array uses the other coder).
+uint32_t decode_blocks(const DecArr& d, int chunk_log2, bool huff);
+// Decode A arrays (descriptors in device memory).  *_prefix_dev[a] is the first
+// workgroup of array a in each launch (A entries); lut holds 2^13 entries per array.
+void launch_decode(const DecArr* arrs_dev, int A, const uint32_t* huff_prefix_dev,
+                   uint32_t huff_blocks, const uint32_t* fixed_prefix_dev, uint32_t fixed_blocks,
+                   int chunk_log2, uint64_t bytes, uint32_t* lut, uint32_t* err, hipStream_t s);
 
 }  // namespace lcp

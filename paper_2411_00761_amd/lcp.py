@@ -20,7 +20,7 @@ EB_ABS, EB_REL_GLOBAL, EB_REL_PER_FIELD = 0, 1, 2
 METHOD_AUTO, METHOD_S, METHOD_T = 0, 1, 2
 DECIDE_S, DECIDE_T, DECIDE_COMPARE = 1, 2, 3
 
-EXPORTED = ["lcp_plan", "lcp_plan_destroy", "lcp_plan_block_log2", "lcp_bound", "lcp_compress",
+EXPORTED = ["lcp_plan", "lcp_plan_destroy", "lcp_plan_reset", "lcp_plan_block_log2", "lcp_bound", "lcp_compress",
             "lcp_decompress", "lcp_select", "lcp_status_string", "lcp_kernel_timer_set",
             "lcp_kernel_timer_read"]
 
@@ -66,6 +66,7 @@ def lib():
         L.lcp_plan.argtypes = [C.POINTER(lcp_params), P, C.c_uint64, C.POINTER(P)]
         L.lcp_plan_destroy.argtypes = [P]
         L.lcp_plan_destroy.restype = None
+        L.lcp_plan_reset.argtypes = [P]
         L.lcp_plan_block_log2.argtypes = [P]
         L.lcp_bound.argtypes = [P, C.c_uint64]
         L.lcp_bound.restype = C.c_uint64
@@ -126,6 +127,9 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    def reset(self):
+        _check(lib().lcp_plan_reset(self.h), "lcp_plan_reset")
 
     @property
     def block_log2(self) -> int:

@@ -166,3 +166,44 @@ def test_forced_temporal_identical_frame(lcp):
     dplan = lcp.Plan(1e-3, lcp.EB_ABS, multi_frame=True, batch_size=0, block_log2=6, max_particles=n)
     d0, d1 = dplan.decompress(out, offs)
     assert torch.equal(d0, d1)
+
+
+def test_temporal_infeasible_falls_back_to_spatial(lcp):
+    """A frame that leaves the reference grid's float32 margin cannot be coded by
+    LCP-T; the stream codes it spatially, exactly as the oracle does."""
+    n = 20000
+    traj = datagen.MDTrajectory(n, seed=31, step=0.001)
+    xs = [traj.next_frame() for _ in range(6)]
+    xs[4] = xs[4] * np.float32(3.0)  # |x| crosses into a higher binade
+    ost = O.Stream(O.EB_REL_GLOBAL, 1e-4, batch_size=0, block_log2=4, max_n=n)
+    plan = lcp.Plan(1e-4, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=0, block_log2=4,
+                    max_particles=n)
+    for t, x in enumerate(xs):
+        want, wused, _ = ost.compress(x)
+        out, offs, used, _ = plan.compress([torch.from_numpy(x).cuda()])
+        rec = out[offs[0]:offs[1]].cpu().numpy().tobytes()
+        assert used[0] == wused, t
+        assert rec == want, f"frame {t}: " + diff_report(rec, want)
+    assert fmt_ref.parse(want)["mode"] in (0, 1)
+
+
+def test_batched_decompress_equals_per_frame(lcp):
+    n, frames = 40000, 20
+    traj = datagen.MDTrajectory(n, seed=41, step=0.003)
+    xs = [torch.from_numpy(traj.next_frame()).cuda() for _ in range(frames)]
+    plan = lcp.Plan(1e-4, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=8, block_log2=5,
+                    max_particles=n)
+    out, offs, used, _ = plan.compress(xs)
+    assert lcp.METHOD_T in used and lcp.METHOD_S in used
+    d_all = lcp.Plan(1e-4, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=8, block_log2=5,
+                     max_particles=n)
+    d_one = lcp.Plan(1e-4, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=8, block_log2=5,
+                     max_particles=n)
+    batch = d_all.decompress(out, offs)
+    ost = O.Stream(O.EB_REL_GLOBAL, 1e-4, batch_size=8, block_log2=5, max_n=n)
+    for j in range(frames):
+        one = d_one.decompress(out, offs[j:j + 2])[0]
+        assert torch.equal(one.view(torch.int32), batch[j].view(torch.int32)), j
+        rec = out[offs[j]:offs[j + 1]].cpu().numpy().tobytes()
+        w = ost.decompress(rec)
+        assert all(bits_equal(batch[j][f].cpu().numpy(), w[f]) for f in range(3)), j
