@@ -32,54 +32,126 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
 }
 
 // ------------------------------------------------------------------ histogram
-__global__ __launch_bounds__(kThreads) void k_enc_init(ArrWork* W, ArrSet set) {
-  ArrWork& w = W[blockIdx.x];
-  for (int j = threadIdx.x; j < kAlphabet; j += blockDim.x) w.hist[j] = 0;
-  if (threadIdx.x == 0) {
-    w.maxv = 0;
-    w.n = 0;
-  }
-}
-
+// Each workgroup counts its share of one array in LDS and writes the whole
+// histogram as a partial (coalesced); a second kernel sums the partials per bin.
 // Lanes of a wave holding the same symbol are grouped by 13 ballots (one per
 // symbol bit); the lowest lane of each group adds the group's size, so a wave
 // of identical symbols (e.g. zero residuals) costs one LDS atomic, not 64.
-__global__ __launch_bounds__(kThreads) void k_hist(ArrSet set, ArrWork* W) {
+// Symbols below kPrivBins are counted in a private LDS histogram per wave (no
+// other wave touches it, and a wave's group leaders hold distinct symbols), the
+// rest in the workgroup's shared histogram with atomics.  A workgroup writes only
+// the bins up to the symbol of its largest value; the reduction reads each
+// partial up to the same bound.
+constexpr int kPrivBins = 256;
+constexpr int kHistVals = 8;  // values per lane per iteration, loads issued together
+
+// Lanes holding the same symbol are grouped by peeling: the first pending lane's
+// symbol is broadcast, its peers found with one ballot, and one of them adds the
+// group size.  The loop runs once per distinct symbol in the wave (a handful for
+// temporal residuals), mostly scalar instructions.
+__device__ inline void hist_group_add(uint32_t* h, uint32_t* hp, uint32_t sym, bool valid,
+                                      uint64_t lt) {
+  (void)lt;
+  uint64_t todo = __ballot(valid);
+  while (todo) {
+    const int l = __ffsll((long long)todo) - 1;
+    const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)sym, l);
+    const uint64_t m = __ballot(sym == s0) & todo;
+    if (lane_id() == l) {
+      const uint32_t cnt = (uint32_t)__popcll(m);
+      if (s0 < (uint32_t)kPrivBins) hp[s0] += cnt;
+      else atomicAdd(&h[s0], cnt);
+    }
+    todo &= ~m;
+  }
+}
+
+__device__ inline int sym_bound(unsigned long long mx) {
+  int e;
+  return symbol_of(mx, &e);
+}
+
+__global__ __launch_bounds__(kThreads) void k_hist(ArrSet set, uint32_t* part,
+                                                   unsigned long long* part_max) {
   __shared__ uint32_t h[kAlphabet];
+  __shared__ uint32_t hpriv[kThreads / kWave][kPrivBins];
+  __shared__ unsigned long long smax[kThreads / kWave];
   const ArrIn a = set.a[blockIdx.y];
-  ArrWork& w = W[blockIdx.y];
   const uint64_t n = arr_len(a);
   for (int j = threadIdx.x; j < kAlphabet; j += kThreads) h[j] = 0;
+  for (int j = threadIdx.x; j < kPrivBins * (kThreads / kWave); j += kThreads) (&hpriv[0][0])[j] = 0;
   __syncthreads();
+  uint32_t* hp = hpriv[wave_id()];
   uint64_t mx = 0;
   const uint64_t lt = lanemask_lt();
-  const uint64_t stride = (uint64_t)gridDim.x * kThreads;
-  for (uint64_t base = (uint64_t)blockIdx.x * kThreads + wave_id() * kWave; base < n;
+  const uint64_t stride = (uint64_t)gridDim.x * kThreads * kHistVals;
+  for (uint64_t base = ((uint64_t)blockIdx.x * kThreads + wave_id() * kWave) * kHistVals; base < n;
        base += stride) {
-    const uint64_t i = base + lane_id();
-    const bool valid = i < n;
-    uint64_t v = valid ? arr_load(a, i) : 0;
-    int e;
-    const uint32_t sym = (uint32_t)symbol_of(v, &e);
-    uint64_t peers = __ballot(valid);
+    uint64_t v[kHistVals];
 #pragma unroll
-    for (int b = 0; b < 13; b++) {
-      uint64_t bal = __ballot((sym >> b) & 1u);
-      peers &= ((sym >> b) & 1u) ? bal : ~bal;
+    for (int j = 0; j < kHistVals; j++) {
+      const uint64_t i = base + (uint64_t)j * kWave + lane_id();
+      v[j] = i < n ? arr_load(a, i) : 0;
     }
-    if (valid && (peers & lt) == 0) atomicAdd(&h[sym], (uint32_t)__popcll(peers));
-    mx = v > mx ? v : mx;
+#pragma unroll
+    for (int j = 0; j < kHistVals; j++) {
+      int e;
+      const bool valid = base + (uint64_t)j * kWave + lane_id() < n;
+      hist_group_add(h, hp, (uint32_t)symbol_of(v[j], &e), valid, lt);
+      mx = v[j] > mx ? v[j] : mx;
+    }
   }
-  __syncthreads();
-  for (int j = threadIdx.x; j < kAlphabet; j += kThreads)
-    if (h[j]) atomicAdd(&w.hist[j], h[j]);
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) {
     uint64_t o = shfl_xor_u64(mx, d);
     mx = o > mx ? o : mx;
   }
-  if (lane_id() == 0 && mx) atomicMax(&w.maxv, (unsigned long long)mx);
-  if (blockIdx.x == 0 && threadIdx.x == 0) w.n = (uint32_t)n;
+  if (lane_id() == 0) smax[wave_id()] = mx;
+  __syncthreads();
+  unsigned long long bm = 0;
+  for (int w = 0; w < kThreads / kWave; w++) bm = smax[w] > bm ? smax[w] : bm;
+  const int top = sym_bound(bm);
+  // add the non-zero bins into one of kHistCopies spread copies of the array's
+  // histogram (few workgroups share an address, so the atomics do not queue)
+  const int copy = blockIdx.x % kHistCopies;
+  uint32_t* dst = part + ((uint64_t)blockIdx.y * kHistCopies + copy) * kAlphabet;
+  for (int j = threadIdx.x; j <= top; j += kThreads) {
+    uint32_t t = h[j];
+    if (j < kPrivBins)
+      for (int w = 0; w < kThreads / kWave; w++) t += hpriv[w][j];
+    if (t) atomicAdd(&dst[j], t);
+  }
+  if (threadIdx.x == 0 && bm)
+    atomicMax(&part_max[(uint64_t)blockIdx.y * kHistCopies + copy], bm);
+}
+
+// Sums the spread copies per bin and clears them for the next use.
+__global__ __launch_bounds__(kThreads) void k_hist_reduce(ArrSet set, uint32_t* part,
+                                                          unsigned long long* part_max,
+                                                          ArrWork* W) {
+  const int a = blockIdx.y;
+  ArrWork& w = W[a];
+  uint32_t* src = part + (uint64_t)a * kHistCopies * kAlphabet;
+  const int j = blockIdx.x * kThreads + threadIdx.x;
+  if (j < kAlphabet) {
+    uint32_t t = 0;
+#pragma unroll
+    for (int c = 0; c < kHistCopies; c++) {
+      t += src[(uint64_t)c * kAlphabet + j];
+      src[(uint64_t)c * kAlphabet + j] = 0;
+    }
+    w.hist[j] = t;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    unsigned long long m = 0;
+    for (int c = 0; c < kHistCopies; c++) {
+      unsigned long long v = part_max[(uint64_t)a * kHistCopies + c];
+      m = v > m ? v : m;
+      part_max[(uint64_t)a * kHistCopies + c] = 0;
+    }
+    w.maxv = m;
+    w.n = (uint32_t)arr_len(set.a[a]);
+  }
 }
 
 // ------------------------------------------------------------------ Huffman build
@@ -109,7 +181,14 @@ __device__ inline uint32_t block_max_u32(uint32_t v, uint32_t* misc) {
   return t;
 }
 
-__global__ __launch_bounds__(kHT) void k_huffman(ArrWork* W) {
+// Code lengths for one array and one halving count h (workgroup (a, h)): counts
+// c -> ceil(c / 2) applied h times, then one Huffman build.  The oracle's loop
+// (halve until the longest code fits) is the smallest h whose build fits; all
+// candidate h run side by side and k_huff_codes picks that smallest one.
+constexpr int kHalvings = 32;  // counts < 2^31: after 31 halvings every count is 1
+
+__global__ __launch_bounds__(kHT) void k_huff_lengths(const ArrWork* W, uint8_t* lens_all,
+                                                      uint32_t* maxd_all) {
   __shared__ uint64_t sm64[8192];
   uint8_t* smb = reinterpret_cast<uint8_t*>(sm64);
   uint32_t* leafw = reinterpret_cast<uint32_t*>(smb);
@@ -118,13 +197,195 @@ __global__ __launch_bounds__(kHT) void k_huffman(ArrWork* W) {
   uint32_t* intw = reinterpret_cast<uint32_t*>(smb + kOffInt);
   uint16_t* anc = reinterpret_cast<uint16_t*>(smb + kOffInt);
   uint16_t* parent = reinterpret_cast<uint16_t*>(smb + kOffParent);
-  uint8_t* lens = smb + kOffLens;
   uint32_t* misc = reinterpret_cast<uint32_t*>(smb + kOffMisc);
 
-  ArrWork& w = W[blockIdx.x];
+  const int a = blockIdx.x, halvings = blockIdx.y;
+  const ArrWork& w = W[a];
   const int t = threadIdx.x;
-  const uint32_t n = w.n;
-  if (n == 0) {
+  uint8_t* lens = lens_all + ((uint64_t)a * kHalvings + halvings) * kAlphabet;
+  uint32_t* maxd = maxd_all + (uint64_t)a * kHalvings + halvings;
+  if (w.n == 0) {
+    if (t == 0) *maxd = 0;
+    return;
+  }
+  constexpr int kPer = (kAlphabet + kHT - 1) / kHT;  // 5 symbols per thread
+  // ---- leaves: used symbols with their halved counts
+  uint32_t c[kPer];
+  uint32_t mine = 0;
+#pragma unroll
+  for (int j = 0; j < kPer; j++) {
+    int s = t + kHT * j;
+    uint32_t cc = s < kAlphabet ? w.hist[s] : 0u;
+    for (int h = 0; h < halvings && cc > 1; h++) cc = (cc + 1u) >> 1;
+    c[j] = cc;
+    mine += cc ? 1u : 0u;
+  }
+  uint32_t incl = wave_incl_scan(mine);
+  if (lane_id() == kWave - 1) misc[wave_id()] = incl;
+  __syncthreads();
+  uint32_t before = 0, U = 0;
+  for (int j = 0; j < kHT / kWave; j++) {
+    uint32_t v = misc[j];
+    if (j < wave_id()) before += v;
+    U += v;
+  }
+  __syncthreads();
+  uint32_t pos = before + incl - mine;
+#pragma unroll
+  for (int j = 0; j < kPer; j++) {
+    int s = t + kHT * j;
+    if (c[j]) sm64[pos++] = ((uint64_t)c[j] << 13) | (uint64_t)s;
+  }
+  if (U == 1) {
+    __syncthreads();
+    uint32_t only = (uint32_t)(sm64[0] & 0x1FFFu);
+    for (int s = t; s < kAlphabet; s += kHT) lens[s] = (uint32_t)s == only ? 1 : 0;
+    if (t == 0) *maxd = 1;
+    return;
+  }
+  uint32_t P = 2;
+  while (P < U) P <<= 1;
+  for (uint32_t i = U + t; i < P; i += kHT) sm64[i] = ~0ull;
+  __syncthreads();
+  // ---- bitonic sort of the (count, symbol) keys; all keys distinct
+  for (uint32_t size = 2; size <= P; size <<= 1) {
+    for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
+      for (uint32_t i = t; i < P / 2; i += kHT) {
+        uint32_t lo = 2 * i - (i & (stride - 1));
+        uint32_t hi = lo + stride;
+        bool asc = (lo & size) == 0;
+        uint64_t x = sm64[lo], y = sm64[hi];
+        if ((x > y) == asc) {
+          sm64[lo] = y;
+          sm64[hi] = x;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // ---- unpack leaves to weights and symbols
+  uint64_t kr[8];
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    uint32_t i = t + kHT * j;
+    kr[j] = i < U ? sm64[i] : 0;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 8; j++) {
+    uint32_t i = t + kHT * j;
+    if (i < U) {
+      leafw[i] = (uint32_t)(kr[j] >> 13);
+      leafsym[i] = (uint16_t)(kr[j] & 0x1FFFu);
+    }
+  }
+  __syncthreads();
+  // ---- two-queue merge: leaves in sorted order, internal nodes FIFO in
+  // creation order; the lighter head is taken, the leaf on a tie.  The four
+  // candidates of a step are loaded together; a missing one reads as +inf.
+  if (t == 0) {
+    constexpr uint32_t kInf = 0xFFFFFFFFu;
+    uint32_t li = 0, ii = 0, nxt = 0;
+    for (uint32_t step = 0; step + 1 < U; step++) {
+      const uint32_t L0 = li < U ? leafw[li] : kInf;
+      const uint32_t L1 = li + 1 < U ? leafw[li + 1] : kInf;
+      const uint32_t I0 = ii < nxt ? intw[ii] : kInf;
+      const uint32_t I1 = ii + 1 < nxt ? intw[ii + 1] : kInf;
+      uint32_t node0, node1, w0, w1, lh, ih;
+      if (L0 <= I0) {
+        node0 = li++;
+        w0 = L0;
+        lh = L1;
+        ih = I0;
+      } else {
+        node0 = U + ii++;
+        w0 = I0;
+        lh = L0;
+        ih = I1;
+      }
+      if (lh <= ih) {
+        node1 = li++;
+        w1 = lh;
+      } else {
+        node1 = U + ii++;
+        w1 = ih;
+      }
+      intw[nxt] = w0 + w1;
+      parent[node0] = (uint16_t)(U + nxt);
+      parent[node1] = (uint16_t)(U + nxt);
+      nxt++;
+    }
+  }
+  __syncthreads();
+  // ---- depths by pointer jumping (13 rounds cover any depth < 8192)
+  const uint32_t nodes = 2 * U - 1, root = 2 * U - 2;
+  {
+    uint16_t av[9], dv[9];
+#pragma unroll
+    for (int j = 0; j < 9; j++) {
+      uint32_t i = t + kHT * j;
+      av[j] = i < nodes ? (i == root ? (uint16_t)root : parent[i]) : 0;
+      dv[j] = (i < nodes && i != root) ? 1 : 0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 9; j++) {
+      uint32_t i = t + kHT * j;
+      if (i < nodes) {
+        anc[i] = av[j];
+        dist[i] = dv[j];
+      }
+    }
+    __syncthreads();
+  }
+  for (int it = 0; it < 13; it++) {
+    uint16_t av[9], dv[9];
+#pragma unroll
+    for (int j = 0; j < 9; j++) {
+      uint32_t i = t + kHT * j;
+      if (i < nodes) {
+        uint16_t an = anc[i];
+        dv[j] = (uint16_t)(dist[i] + dist[an]);
+        av[j] = anc[an];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 9; j++) {
+      uint32_t i = t + kHT * j;
+      if (i < nodes) {
+        anc[i] = av[j];
+        dist[i] = dv[j];
+      }
+    }
+    __syncthreads();
+  }
+  for (int s = t; s < kAlphabet; s += kHT) lens[s] = 0;
+  __syncthreads();
+  uint32_t md = 0;
+#pragma unroll
+  for (int j = 0; j < 5; j++) {
+    uint32_t i = t + kHT * j;
+    if (i < U) {
+      md = max(md, (uint32_t)dist[i]);
+      lens[leafsym[i]] = (uint8_t)(dist[i] > 255 ? 255 : dist[i]);
+    }
+  }
+  md = block_max_u32(md, misc);
+  if (t == 0) *maxd = md;
+}
+
+// Picks the fewest halvings whose longest code fits, then canonical codes:
+// shorter first, ties by symbol (RFC 1951 order), and the table of used symbols.
+__global__ __launch_bounds__(kHT) void k_huff_codes(ArrWork* W, const uint8_t* lens_all,
+                                                    const uint32_t* maxd_all) {
+  __shared__ uint8_t lens[kAlphabet];
+  __shared__ uint32_t wcnt[kHT / kWave * 16];
+  __shared__ uint32_t misc[64];
+  const int a = blockIdx.x;
+  ArrWork& w = W[a];
+  const int t = threadIdx.x;
+  if (w.n == 0) {
     for (int s = t; s < kAlphabet; s += kHT) w.lc[s] = 0;
     if (t == 0) {
       w.U = 0;
@@ -132,175 +393,14 @@ __global__ __launch_bounds__(kHT) void k_huffman(ArrWork* W) {
     }
     return;
   }
-  constexpr int kPer = (kAlphabet + kHT - 1) / kHT;  // 5 symbols per thread
-  uint32_t U = 0;
-  for (int halvings = 0;; halvings++) {
-    // ---- leaves: used symbols with their (halved) counts
-    uint32_t c[kPer];
-    uint32_t mine = 0;
-#pragma unroll
-    for (int j = 0; j < kPer; j++) {
-      int s = t + kHT * j;
-      uint32_t cc = s < kAlphabet ? w.hist[s] : 0u;
-      for (int h = 0; h < halvings && cc; h++) cc = (cc + 1u) >> 1;
-      c[j] = cc;
-      mine += cc ? 1u : 0u;
-    }
-    // exclusive position of this thread's leaves
-    uint32_t incl = wave_incl_scan(mine);
-    __syncthreads();
-    if (lane_id() == kWave - 1) misc[wave_id()] = incl;
-    __syncthreads();
-    uint32_t before = 0, total = 0;
-    for (int j = 0; j < kHT / kWave; j++) {
-      uint32_t v = misc[j];
-      if (j < wave_id()) before += v;
-      total += v;
-    }
-    __syncthreads();
-    U = total;
-    uint32_t pos = before + incl - mine;
-#pragma unroll
-    for (int j = 0; j < kPer; j++) {
-      int s = t + kHT * j;
-      if (c[j]) sm64[pos++] = ((uint64_t)c[j] << 13) | (uint64_t)s;
-    }
-    if (U == 1) {
-      __syncthreads();
-      uint32_t only = (uint32_t)(sm64[0] & 0x1FFFu);
-      __syncthreads();
-      for (int s = t; s < kAlphabet; s += kHT) lens[s] = (uint32_t)s == only ? 1 : 0;
-      __syncthreads();
-      break;
-    }
-    uint32_t P = 2;
-    while (P < U) P <<= 1;
-    for (uint32_t i = U + t; i < P; i += kHT) sm64[i] = ~0ull;
-    __syncthreads();
-    // ---- bitonic sort of the (count, symbol) keys; all keys distinct
-    for (uint32_t size = 2; size <= P; size <<= 1) {
-      for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-        for (uint32_t i = t; i < P / 2; i += kHT) {
-          uint32_t lo = 2 * i - (i & (stride - 1));
-          uint32_t hi = lo + stride;
-          bool asc = (lo & size) == 0;
-          uint64_t a = sm64[lo], b = sm64[hi];
-          if ((a > b) == asc) {
-            sm64[lo] = b;
-            sm64[hi] = a;
-          }
-        }
-        __syncthreads();
-      }
-    }
-    // ---- unpack leaves to weights and symbols
-    uint64_t kr[8];
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      uint32_t i = t + kHT * j;
-      kr[j] = i < U ? sm64[i] : 0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int j = 0; j < 8; j++) {
-      uint32_t i = t + kHT * j;
-      if (i < U) {
-        leafw[i] = (uint32_t)(kr[j] >> 13);
-        leafsym[i] = (uint16_t)(kr[j] & 0x1FFFu);
-      }
-    }
-    __syncthreads();
-    // ---- two-queue merge: leaves in sorted order, internal nodes FIFO in
-    // creation order; the lighter head is taken, the leaf on a tie.
-    if (t == 0) {
-      uint32_t li = 0, ii = 0, nxt = 0;
-      for (uint32_t step = 0; step + 1 < U; step++) {
-        uint32_t node0, node1, w0, w1;
-        {
-          bool leaf = li < U && (ii >= nxt || leafw[li] <= intw[ii]);
-          if (leaf) { node0 = li; w0 = leafw[li]; li++; }
-          else { node0 = U + ii; w0 = intw[ii]; ii++; }
-        }
-        {
-          bool leaf = li < U && (ii >= nxt || leafw[li] <= intw[ii]);
-          if (leaf) { node1 = li; w1 = leafw[li]; li++; }
-          else { node1 = U + ii; w1 = intw[ii]; ii++; }
-        }
-        intw[nxt] = w0 + w1;
-        parent[node0] = (uint16_t)(U + nxt);
-        parent[node1] = (uint16_t)(U + nxt);
-        nxt++;
-      }
-    }
-    __syncthreads();
-    // ---- depths by pointer jumping (13 rounds cover any depth < 8192)
-    const uint32_t nodes = 2 * U - 1, root = 2 * U - 2;
-    {
-      uint16_t av[9], dv[9];
-#pragma unroll
-      for (int j = 0; j < 9; j++) {
-        uint32_t i = t + kHT * j;
-        av[j] = i < nodes ? (i == root ? (uint16_t)root : parent[i]) : 0;
-        dv[j] = (i < nodes && i != root) ? 1 : 0;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < 9; j++) {
-        uint32_t i = t + kHT * j;
-        if (i < nodes) {
-          anc[i] = av[j];
-          dist[i] = dv[j];
-        }
-      }
-      __syncthreads();
-    }
-    for (int it = 0; it < 13; it++) {
-      uint16_t av[9], dv[9];
-#pragma unroll
-      for (int j = 0; j < 9; j++) {
-        uint32_t i = t + kHT * j;
-        if (i < nodes) {
-          uint16_t a = anc[i];
-          dv[j] = (uint16_t)(dist[i] + dist[a]);
-          av[j] = anc[a];
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < 9; j++) {
-        uint32_t i = t + kHT * j;
-        if (i < nodes) {
-          anc[i] = av[j];
-          dist[i] = dv[j];
-        }
-      }
-      __syncthreads();
-    }
-    uint32_t md = 0;
-#pragma unroll
-    for (int j = 0; j < 5; j++) {
-      uint32_t i = t + kHT * j;
-      if (i < U) md = max(md, (uint32_t)dist[i]);
-    }
-    md = block_max_u32(md, misc);
-    if (md <= (uint32_t)kMaxLen) {
-      for (int s = t; s < kAlphabet; s += kHT) lens[s] = 0;
-      __syncthreads();
-#pragma unroll
-      for (int j = 0; j < 5; j++) {
-        uint32_t i = t + kHT * j;
-        if (i < U) lens[leafsym[i]] = (uint8_t)dist[i];
-      }
-      __syncthreads();
-      break;
-    }
-    __syncthreads();
-  }
-  // ---- canonical codes: shorter first, then by symbol (RFC 1951 order)
-  uint32_t* wcnt = reinterpret_cast<uint32_t*>(smb);  // [16 waves][16]
-  uint32_t* blc = misc;                               // [16] code-length counts
-  uint32_t* first = misc + 16;                        // [16] first code per length
-  uint32_t* run = misc + 32;                          // [16] codes given so far / table size
+  int hsel = kHalvings - 1;
+  for (int h = kHalvings - 1; h >= 0; h--)
+    if (maxd_all[(uint64_t)a * kHalvings + h] <= (uint32_t)kMaxLen) hsel = h;
+  const uint8_t* src = lens_all + ((uint64_t)a * kHalvings + hsel) * kAlphabet;
+  for (int s = t; s < kAlphabet; s += kHT) lens[s] = src[s];
+  uint32_t* blc = misc;        // [16] code-length counts
+  uint32_t* first = misc + 16; // [16] first code per length
+  uint32_t* run = misc + 32;   // [16] codes given so far / table size
   if (t < 48) misc[t] = 0;
   __syncthreads();
   uint32_t lmax = 0;
@@ -362,26 +462,63 @@ __global__ __launch_bounds__(kHT) void k_huffman(ArrWork* W) {
 }
 
 // ------------------------------------------------------------------ chunk sizes
+// One workgroup per chunk; thread t holds the chunk's symbols [t*r, t*r + r)
+// with r = C / 256 (at least 1), loaded together.
+constexpr int kMaxRun = 16;  // chunk_log2 <= 12
+
+// Code of a symbol: from the workgroup's LDS copy of the first kPrivBins
+// entries, else from the array's table in global memory.
+__device__ inline uint32_t code_of(const ArrWork& w, const uint32_t* lc_lds, int sym) {
+  return sym < kPrivBins ? lc_lds[sym] : w.lc[sym];
+}
+
+__device__ inline void load_codes(const ArrWork& w, uint32_t* lc_lds) {
+  for (int j = threadIdx.x; j < kPrivBins; j += blockDim.x) lc_lds[j] = w.lc[j];
+}
+
+template <int RUN>
+__device__ inline uint32_t run_bits(const ArrIn& in, const ArrWork& w, const uint32_t* lc_lds,
+                                    uint64_t i0, uint64_t i1, uint64_t* vals) {
+#pragma unroll
+  for (int j = 0; j < RUN; j++) vals[j] = i0 + j < i1 ? arr_load(in, i0 + j) : 0;
+  uint32_t bits = 0;
+#pragma unroll
+  for (int j = 0; j < RUN; j++) {
+    int e;
+    int sym = symbol_of(vals[j], &e);
+    if (i0 + j < i1) bits += (code_of(w, lc_lds, sym) >> 16) + (uint32_t)e;
+  }
+  return bits;
+}
+
+template <int RUN>
 __global__ __launch_bounds__(kThreads) void k_chunk_bits(ArrSet set, const ArrWork* W,
                                                          int chunk_log2, uint32_t* cw,
                                                          uint64_t max_chunks) {
+  __shared__ uint32_t sm[kThreads / kWave];
+  __shared__ uint32_t lc_lds[kPrivBins];
   const int a = blockIdx.y;
   const ArrIn in = set.a[a];
   const ArrWork& w = W[a];
   const uint64_t n = w.n;
   const uint64_t C = 1ull << chunk_log2;
   const uint64_t nchunks = (n + C - 1) >> chunk_log2;
-  const uint64_t c = (uint64_t)blockIdx.x * (kThreads / kWave) + wave_id();
-  if (c >= nchunks || w.U == 0) return;
-  const uint64_t end = min(n, (c + 1) * C);
-  uint32_t bits = 0;
-  for (uint64_t i = c * C + lane_id(); i < end; i += kWave) {
-    int e;
-    int sym = symbol_of(arr_load(in, i), &e);
-    bits += (w.lc[sym] >> 16) + (uint32_t)e;
+  if (w.U == 0 || blockIdx.x >= nchunks) return;
+  load_codes(w, lc_lds);
+  __syncthreads();
+  const uint64_t run = C >= (uint64_t)kThreads ? C / kThreads : 1;
+  for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const uint64_t cend = min(n, (c + 1) * C);
+    const uint64_t i0 = min(cend, c * C + threadIdx.x * run);
+    const uint64_t i1 = min(cend, i0 + run);
+    uint64_t vals[RUN];
+    uint32_t bits = wave_sum(run_bits<RUN>(in, w, lc_lds, i0, i1, vals));
+    if (lane_id() == 0) sm[wave_id()] = bits;
+    __syncthreads();
+    if (threadIdx.x == 0)
+      cw[(uint64_t)a * max_chunks + c] = (sm[0] + sm[1] + sm[2] + sm[3] + 31u) >> 5;
+    __syncthreads();
   }
-  bits = wave_sum(bits);
-  if (lane_id() == 0) cw[(uint64_t)a * max_chunks + c] = (bits + 31u) >> 5;
 }
 
 // Inclusive scan of one array's chunk word counts (one workgroup per array).
@@ -514,26 +651,46 @@ __global__ __launch_bounds__(kThreads) void k_pack_fixed(ArrSet set, const ArrWo
   }
 }
 
-__device__ inline void put_bits_lds(uint32_t* buf, uint32_t pos, uint64_t val, int nbits) {
-  while (nbits > 0) {
-    uint32_t wi = pos >> 5, o = pos & 31u;
-    int room = 32 - (int)o;
-    int take = nbits < room ? nbits : room;
-    uint32_t part = (uint32_t)((val >> (nbits - take)) & ((1ull << take) - 1));
-    atomicOr(&buf[wi], part << (room - take));
-    pos += (uint32_t)take;
-    nbits -= take;
+// Bits are appended MSB-first to a 64-bit accumulator and flushed one 32-bit
+// word at a time into the chunk image in LDS (OR, since the first and last word
+// of a lane's run are shared with its neighbours).
+struct BitSink {
+  uint64_t acc;
+  int accb;
+  uint32_t wi;
+  uint32_t* buf;
+  __device__ inline void push(uint64_t val, int nb) {  // nb <= 32
+    if (nb == 0) return;
+    acc = (acc << nb) | val;
+    accb += nb;
+    if (accb >= 32) {
+      atomicOr(&buf[wi], (uint32_t)(acc >> (accb - 32)));
+      wi++;
+      accb -= 32;
+      acc &= accb ? ((1ull << accb) - 1) : 0ull;
+    }
   }
-}
+  __device__ inline void flush() {
+    if (accb > 0) atomicOr(&buf[wi], (uint32_t)(acc << (32 - accb)));
+  }
+};
 
-// One wave per chunk; the chunk's words are assembled in LDS.
-__global__ void k_pack_huff(ArrSet set, const ArrWork* W, int chunk_log2, const uint32_t* cw,
-                            uint64_t max_chunks, uint32_t max_words, uint8_t* out,
-                            const uint32_t* err) {
-  extern __shared__ uint32_t lds[];
+// One workgroup per chunk; thread t packs the t-th run of C/256 consecutive
+// symbols, starting at the bit offset given by a block prefix scan of the runs'
+// lengths, into the chunk's image in LDS, which is then written out coalesced.
+template <int RUN>
+__global__ __launch_bounds__(kThreads) void k_pack_huff(ArrSet set, const ArrWork* W,
+                                                        int chunk_log2, const uint32_t* cw,
+                                                        uint64_t max_chunks, uint32_t max_words,
+                                                        uint8_t* out, const uint32_t* err) {
+  extern __shared__ uint32_t buf[];
+  __shared__ uint32_t sm[kThreads / kWave + 1];
+  __shared__ uint32_t lc_lds[kPrivBins];
   const int a = blockIdx.y;
   const ArrWork& w = W[a];
   if (w.coder != 1 || (*err & kErrCapacity)) return;
+  load_codes(w, lc_lds);
+  __syncthreads();
   const ArrIn in = set.a[a];
   const uint64_t n = w.n, nchunks = w.nchunks, U = w.U;
   uint32_t* tab = reinterpret_cast<uint32_t*>(out + w.off);
@@ -544,40 +701,46 @@ __global__ void k_pack_huff(ArrSet set, const ArrWork* W, int chunk_log2, const 
   const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t j = gid; j < U; j += gstride) tab[j] = w.table[j];
   for (uint64_t c = gid; c < nchunks; c += gstride) offs[c] = ce[c];
-
-  const int waves = (int)(blockDim.x / kWave);
-  const uint64_t c = (uint64_t)blockIdx.x * waves + wave_id();
-  const bool active = c < nchunks;
-  const uint32_t wbeg = active ? (c ? ce[c - 1] : 0u) : 0u;
-  const uint32_t nw = active ? ce[c] - wbeg : 0u;
-  uint32_t* buf = lds + (uint64_t)wave_id() * max_words;
-  const bool fits = nw <= max_words;
-  for (uint32_t j = lane_id(); j < nw && fits; j += kWave) buf[j] = 0;
-  __syncthreads();
-  if (active && fits) {
-    const uint64_t C = 1ull << chunk_log2;
-    const uint64_t end = min(n, (c + 1) * C);
-    uint32_t run = 0;
-    for (uint64_t i0 = c * C; i0 < end; i0 += kWave) {
-      const uint64_t i = i0 + lane_id();
-      const bool valid = i < end;
-      uint64_t v = valid ? arr_load(in, i) : 0;
-      int e;
-      int sym = symbol_of(v, &e);
-      uint32_t lc = valid ? w.lc[sym] : 0u;
-      uint32_t len = lc >> 16;
-      uint32_t bits = valid ? len + (uint32_t)e : 0u;
-      uint32_t incl = wave_incl_scan(bits);
-      uint32_t pos = run + incl - bits;
-      run += (uint32_t)__shfl((int)incl, kWave - 1, kWave);
-      if (valid) {
-        put_bits_lds(buf, pos, lc & 0xFFFFu, (int)len);
-        if (e) put_bits_lds(buf, pos + len, v - (1ull << e), e);
+  const uint64_t C = 1ull << chunk_log2;
+  const uint64_t run = C >= (uint64_t)kThreads ? C / kThreads : 1;
+  for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const uint32_t wbeg = c ? ce[c - 1] : 0u;
+    const uint32_t nw = ce[c] - wbeg;
+    const bool fits = nw <= max_words;
+    for (uint32_t j = threadIdx.x; j < nw && fits; j += kThreads) buf[j] = 0;
+    const uint64_t cend = min(n, (c + 1) * C);
+    const uint64_t i0 = min(cend, c * C + threadIdx.x * run);
+    const uint64_t i1 = min(cend, i0 + run);
+    uint64_t vals[RUN];
+    const uint32_t bits = run_bits<RUN>(in, w, lc_lds, i0, i1, vals);
+    uint32_t total;
+    const uint32_t start = block_incl_scan(bits, sm, &total) - bits;
+    if (bits && fits) {
+      BitSink sk{0ull, (int)(start & 31u), start >> 5, buf};
+#pragma unroll
+      for (int j = 0; j < RUN; j++) {
+        if (i0 + j >= i1) break;
+        const uint64_t v = vals[j];
+        int e;
+        const int sym = symbol_of(v, &e);
+        const uint32_t lc = code_of(w, lc_lds, sym);
+        sk.push(lc & 0xFFFFu, (int)(lc >> 16));
+        if (e) {
+          const uint64_t x = v - (1ull << e);
+          if (e > 32) {
+            sk.push(x >> 32, e - 32);
+            sk.push(x & 0xFFFFFFFFull, 32);
+          } else {
+            sk.push(x, e);
+          }
+        }
       }
+      sk.flush();
     }
+    __syncthreads();
+    for (uint32_t j = threadIdx.x; j < nw && fits; j += kThreads) payload[wbeg + j] = buf[j];
+    __syncthreads();
   }
-  __syncthreads();
-  for (uint32_t j = lane_id(); j < nw && fits; j += kWave) payload[wbeg + j] = buf[j];
 }
 
 // ------------------------------------------------------------------ decode
@@ -688,13 +851,162 @@ __device__ inline bool store_value(const DecArr& d, uint64_t i, uint64_t v) {
   return true;
 }
 
-// One thread per chunk; the array's lookup table is staged in LDS.
+// One thread per chunk; the array's lookup table is staged in LDS.  32-bit
+// outputs go through an LDS tile: every round each thread decodes kRound
+// symbols of its chunk, then the workgroup writes the 256 x kRound tile back as
+// 64-byte segments (one cache-line half per 16 lanes) instead of 64 scattered
+// words per store.
+constexpr int kRound = 16;
+
+// MSB-first reader over one chunk's words.  Two words are always in flight
+// ahead of the 64-bit window, so the global load a lane needs next was issued
+// tens of symbols earlier instead of stalling the (divergent) refill.
+struct BitReader {
+  uint64_t buf;
+  int nb;
+  uint64_t wp, wend;  // next word to load, end of the chunk
+  uint32_t n0, n1;    // prefetched words
+  int have;           // how many of n0, n1 are valid
+  const uint32_t* payload;
+  __device__ inline void start(const uint32_t* p, uint64_t beg, uint64_t end) {
+    payload = p;
+    wp = beg;
+    wend = end;
+    buf = 0;
+    nb = 0;
+    have = 0;
+    n0 = wp < wend ? payload[wp] : 0u;
+    if (wp < wend) { wp++; have = 1; }
+    n1 = wp < wend ? payload[wp] : 0u;
+    if (wp < wend) { wp++; have = 2; }
+  }
+  __device__ inline void refill() {
+    while (nb <= 32 && have > 0) {
+      buf |= (uint64_t)n0 << (32 - nb);
+      nb += 32;
+      n0 = n1;
+      have--;
+      if (wp < wend) {
+        n1 = payload[wp++];
+        have++;
+      }
+    }
+  }
+};
+
+// Raw bits that follow a length-class symbol (rare): up to 63 bits.
+__device__ inline bool read_extra(BitReader& r, int eb, uint64_t* x) {
+  uint64_t v = 0;
+  int rem = eb;
+  while (rem > 0) {
+    r.refill();
+    const int take = rem < 32 ? rem : 32;
+    if (take > r.nb) return false;
+    v = (v << take) | (r.buf >> (64 - take));
+    r.buf <<= take;
+    r.nb -= take;
+    rem -= take;
+  }
+  *x = v;
+  return true;
+}
+
+template <int MODE>
+__device__ inline void put_value(const DecArr& d, uint32_t* tile_slot, uint64_t i, uint64_t v) {
+  if (MODE == 0) reinterpret_cast<uint64_t*>(d.out)[i] = v;
+  else if (MODE == 1) reinterpret_cast<uint64_t*>(d.out)[i] = (uint64_t)unzigzag64(v);
+  else if (MODE == 2) *tile_slot = (uint32_t)v;
+  else *tile_slot = (uint32_t)(int32_t)unzigzag64(v);
+}
+
+// Decodes up to kRound symbols of one chunk; returns false on a malformed stream.
+// A refill always leaves at least 33 bits, so one test per symbol suffices for
+// the code itself (at most 13 bits).
+template <int MODE>
+__device__ inline bool decode_round(BitReader& r, const uint32_t* lut, int L, const DecArr& d,
+                                    uint64_t i0, int cnt, uint32_t* tile_row) {
+  for (int j = 0; j < cnt; j++) {
+    if (r.nb <= 32) r.refill();
+    const uint32_t e = lut[(uint32_t)(r.buf >> (64 - L))];
+    const int l = (int)(e >> 16);
+    if (l == 0 || l > r.nb) return false;
+    const uint32_t sym = e & 0xFFFFu;
+    r.buf <<= l;
+    r.nb -= l;
+    uint64_t v = sym;
+    if (sym >= (uint32_t)kDirect) {
+      const int eb = (int)sym - kDirect + kFirstClassBits - 1;
+      uint64_t x;
+      if (!read_extra(r, eb, &x)) return false;
+      v = (1ull << eb) + x;
+    }
+    if (v >= d.limit) return false;
+    put_value<MODE>(d, tile_row + j, i0 + j, v);
+  }
+  return true;
+}
+
+template <int MODE>
+__device__ inline void decode_chunks(const DecArr& d, const uint32_t* lut, int L,
+                                     uint64_t c0, int chunk_log2, uint32_t* tile, uint32_t* err) {
+  const uint64_t C = 1ull << chunk_log2;
+  const uint64_t nchunks = (d.n + C - 1) >> chunk_log2;
+  const uint64_t c = c0 + threadIdx.x;
+  const uint32_t* offs = reinterpret_cast<const uint32_t*>(d.data) + d.used;
+  const uint64_t payload_words = d.nbytes / 4 - d.used - nchunks;
+  BitReader r;
+  r.start(offs + nchunks, 0, 0);
+  bool ok = c < nchunks;
+  uint64_t cbeg = 0, cend = 0;
+  if (ok) {
+    const uint64_t wbeg = c ? offs[c - 1] : 0, wend = offs[c];
+    if (wbeg > wend || wend > payload_words || (c == nchunks - 1 && wend != payload_words)) {
+      atomicOr(err, kErrCorrupt);
+      ok = false;
+    } else {
+      r.start(offs + nchunks, wbeg, wend);
+    }
+    cbeg = c * C;
+    cend = min(d.n, cbeg + C);
+  }
+  constexpr bool kWide = MODE < 2;  // 64-bit outputs (block ids / counts): stored directly
+  const uint64_t rounds = (min(C, d.n - min(d.n, c0 * C)) + kRound - 1) / kRound;
+  uint32_t* row = tile + threadIdx.x * (kRound + 1);
+  for (uint64_t rd = 0; rd < rounds; rd++) {
+    const uint64_t i0 = cbeg + rd * kRound;
+    if (ok && i0 < cend) {
+      const int cnt = (int)min((uint64_t)kRound, cend - i0);
+      if (!decode_round<MODE>(r, lut, L, d, i0, cnt, row)) {
+        atomicOr(err, kErrCorrupt);
+        ok = false;
+      }
+    }
+    if (kWide) continue;
+    __syncthreads();
+    // 16 lanes per 64-byte segment: segment = one chunk's kRound values this round
+    const int sub = lane_id() & 15;
+    for (int seg = wave_id() * 64 + (lane_id() >> 4); seg < wave_id() * 64 + 64; seg += 4) {
+      const uint64_t cc = c0 + seg;
+      const uint64_t i = cc * C + rd * kRound + sub;
+      if (cc < nchunks && i < min(d.n, (cc + 1) * C))
+        reinterpret_cast<uint32_t*>(d.out)[i] = tile[seg * (kRound + 1) + sub];
+    }
+    __syncthreads();
+  }
+}
+
+// One thread per chunk; the array's lookup table is staged in LDS.  32-bit
+// outputs go through an LDS tile: every round each thread decodes kRound
+// symbols of its chunk, then the workgroup writes the 256 x kRound tile back as
+// 64-byte segments (one cache-line half per 16 lanes) instead of 64 scattered
+// words per store.
 __global__ __launch_bounds__(kThreads) void k_decode_huff(const DecArr* arrs,
                                                           const uint32_t* prefix, int A,
                                                           int chunk_log2,
                                                           const uint32_t* lut_all,
                                                           uint32_t* err) {
   __shared__ uint32_t lut[1u << kMaxLen];
+  __shared__ uint32_t tile[kThreads * (kRound + 1)];
   const uint32_t a = array_of_block(prefix, A, blockIdx.x);
   const DecArr d = arrs[a];
   if (d.coder != 1 || d.param < 1 || d.param > kMaxLen || (*err & kErrCorrupt)) return;
@@ -702,64 +1014,12 @@ __global__ __launch_bounds__(kThreads) void k_decode_huff(const DecArr* arrs,
   const uint32_t* src = lut_all + (uint64_t)a * (1u << kMaxLen);
   for (uint32_t i = threadIdx.x; i < (1u << L); i += kThreads) lut[i] = src[i];
   __syncthreads();
-  const uint64_t C = 1ull << chunk_log2;
-  const uint64_t nchunks = (d.n + C - 1) >> chunk_log2;
-  const uint64_t c = (uint64_t)(blockIdx.x - prefix[a]) * kThreads + threadIdx.x;
-  if (c >= nchunks) return;
-  const uint32_t* offs = reinterpret_cast<const uint32_t*>(d.data) + d.used;
-  const uint32_t* payload = offs + nchunks;
-  const uint64_t payload_words = d.nbytes / 4 - d.used - nchunks;
-  const uint64_t wbeg = c ? offs[c - 1] : 0, wend = offs[c];
-  if (wbeg > wend || wend > payload_words || (c == nchunks - 1 && wend != payload_words)) {
-    atomicOr(err, kErrCorrupt);
-    return;
-  }
-  uint64_t buf = 0;
-  int nb = 0;
-  uint64_t wp = wbeg;
-  const uint64_t end = min(d.n, (c + 1) * C);
-  for (uint64_t i = c * C; i < end; i++) {
-    while (nb <= 32 && wp < wend) {
-      buf |= (uint64_t)payload[wp] << (32 - nb);
-      wp++;
-      nb += 32;
-    }
-    const uint32_t e = lut[(uint32_t)(buf >> (64 - L))];
-    const int l = (int)((e >> 16) & 0xFFu);
-    if (l == 0 || l > nb) {
-      atomicOr(err, kErrCorrupt);
-      return;
-    }
-    const uint32_t sym = e & 0xFFFFu;
-    buf <<= l;
-    nb -= l;
-    uint64_t v = sym;
-    if (sym >= (uint32_t)kDirect) {
-      const int eb = (int)sym - kDirect + kFirstClassBits - 1;
-      uint64_t x = 0;
-      int rem = eb;
-      while (rem > 0) {
-        while (nb <= 32 && wp < wend) {
-          buf |= (uint64_t)payload[wp] << (32 - nb);
-          wp++;
-          nb += 32;
-        }
-        const int take = rem < 32 ? rem : 32;
-        if (take > nb) {
-          atomicOr(err, kErrCorrupt);
-          return;
-        }
-        x = (x << take) | (buf >> (64 - take));
-        buf <<= take;
-        nb -= take;
-        rem -= take;
-      }
-      v = (1ull << eb) + x;
-    }
-    if (!store_value(d, i, v)) {
-      atomicOr(err, kErrCorrupt);
-      return;
-    }
+  const uint64_t c0 = (uint64_t)(blockIdx.x - prefix[a]) * kThreads;
+  switch (d.mode) {
+    case 0: decode_chunks<0>(d, lut, L, c0, chunk_log2, tile, err); break;
+    case 1: decode_chunks<1>(d, lut, L, c0, chunk_log2, tile, err); break;
+    case 2: decode_chunks<2>(d, lut, L, c0, chunk_log2, tile, err); break;
+    default: decode_chunks<3>(d, lut, L, c0, chunk_log2, tile, err); break;
   }
 }
 
@@ -799,39 +1059,55 @@ inline uint32_t gclamp(uint64_t g, uint32_t cap) {
 }  // namespace
 
 void launch_encode(const ArrSet& set, uint64_t max_n, int chunk_log2, ArrWork* work,
-                   uint32_t* chunk_words, uint64_t max_chunks, const RecHdr& h,
-                   const uint32_t* B_dev, uint8_t* out, uint64_t cap,
+                   uint32_t* chunk_words, uint64_t max_chunks, uint32_t* hist_part,
+                   unsigned long long* hist_max, uint8_t* huff_lens, uint32_t* huff_maxd,
+                   const RecHdr& h, const uint32_t* B_dev, uint8_t* out, uint64_t cap,
                    unsigned long long* size_dev, uint32_t* err, hipStream_t s) {
   const int A = set.A;
-  k_enc_init<<<A, kThreads, 0, s>>>(work, set);
   {
-    dim3 g(gclamp((max_n + 4 * kThreads - 1) / (4 * kThreads), 512), A);
-    LCP_TIMED("hist", max_n * 4ull * A, s, k_hist<<<g, kThreads, 0, s>>>(set, work));
+    const int nb = (int)gclamp((max_n + 8191) / 8192, kHistBlocks);
+    dim3 g(nb, A);
+    LCP_TIMED("hist", max_n * 4ull * A, s, k_hist<<<g, kThreads, 0, s>>>(set, hist_part, hist_max));
+    k_hist_reduce<<<dim3((kAlphabet + kThreads - 1) / kThreads, A), kThreads, 0, s>>>(
+        set, hist_part, hist_max, work);
   }
-  k_huffman<<<A, kHT, 0, s>>>(work);
+  k_huff_lengths<<<dim3(A, kHalvings), kHT, 0, s>>>(work, huff_lens, huff_maxd);
+  k_huff_codes<<<A, kHT, 0, s>>>(work, huff_lens, huff_maxd);
   const uint64_t chunks = (max_n + (1ull << chunk_log2) - 1) >> chunk_log2;
   {
-    dim3 g(gclamp((chunks + 3) / 4, 1u << 30), A);
-    k_chunk_bits<<<g, kThreads, 0, s>>>(set, work, chunk_log2, chunk_words, max_chunks);
+    dim3 g(gclamp(chunks, 1024), A);
+    LCP_TIMED("chunk_bits", max_n * 4ull * A, s, {
+      switch (chunk_log2) {
+        case 9: k_chunk_bits<2><<<g, kThreads, 0, s>>>(set, work, chunk_log2, chunk_words, max_chunks); break;
+        case 10: k_chunk_bits<4><<<g, kThreads, 0, s>>>(set, work, chunk_log2, chunk_words, max_chunks); break;
+        case 11: k_chunk_bits<8><<<g, kThreads, 0, s>>>(set, work, chunk_log2, chunk_words, max_chunks); break;
+        case 12: k_chunk_bits<16><<<g, kThreads, 0, s>>>(set, work, chunk_log2, chunk_words, max_chunks); break;
+        default: k_chunk_bits<1><<<g, kThreads, 0, s>>>(set, work, chunk_log2, chunk_words, max_chunks); break;
+      }
+    });
   }
   k_chunk_scan<<<A, kHT, 0, s>>>(work, chunk_log2, chunk_words, max_chunks);
   k_layout<<<1, 64, 0, s>>>(work, h, B_dev, out, cap, size_dev, err);
   {
     const uint64_t max_words = (max_n * 64 + 31) / 32;
-    dim3 g(gclamp((max_words + kThreads - 1) / kThreads, 1u << 16), A);
+    dim3 g(gclamp((max_words + kThreads - 1) / kThreads, 2048), A);
     LCP_TIMED("pack_fixed", max_n * 6ull * A, s,
               k_pack_fixed<<<g, kThreads, 0, s>>>(set, work, out, err));
   }
   {
     const uint32_t C = 1u << chunk_log2;
     const uint32_t max_words = (C * (kMaxLen + 63) + 31) / 32 + 1;
-    int waves = (int)((64 * 1024) / (max_words * 4));
-    if (waves > 4) waves = 4;
-    if (waves < 1) waves = 1;
-    dim3 g(gclamp((chunks + waves - 1) / waves, 1u << 30), A);
-    LCP_TIMED("pack_huff", max_n * 6ull * A, s,
-              k_pack_huff<<<g, waves * kWave, (size_t)waves * max_words * 4, s>>>(
-                  set, work, chunk_log2, chunk_words, max_chunks, max_words, out, err));
+    dim3 g(gclamp(chunks, 1024), A);
+    const size_t shm = (size_t)max_words * 4;
+    LCP_TIMED("pack_huff", max_n * 6ull * A, s, {
+      switch (chunk_log2) {
+        case 9: k_pack_huff<2><<<g, kThreads, shm, s>>>(set, work, chunk_log2, chunk_words, max_chunks, max_words, out, err); break;
+        case 10: k_pack_huff<4><<<g, kThreads, shm, s>>>(set, work, chunk_log2, chunk_words, max_chunks, max_words, out, err); break;
+        case 11: k_pack_huff<8><<<g, kThreads, shm, s>>>(set, work, chunk_log2, chunk_words, max_chunks, max_words, out, err); break;
+        case 12: k_pack_huff<16><<<g, kThreads, shm, s>>>(set, work, chunk_log2, chunk_words, max_chunks, max_words, out, err); break;
+        default: k_pack_huff<1><<<g, kThreads, shm, s>>>(set, work, chunk_log2, chunk_words, max_chunks, max_words, out, err); break;
+      }
+    });
   }
 }
 

@@ -344,34 +344,61 @@ __global__ __launch_bounds__(kThreads) void k_slot_syms(FieldPtrs x, int F, uint
 // minus the reference codes (zigzag); the new codes become the next reference.
 // The frame must stay inside the grid's float32 margin (|x| + 2 eb < 2^E) and
 // code range (|2q+1| < 2^24); a particle outside it flags the frame.
+__device__ inline uint32_t t_code(float xv, const GridDev& g, int f, uint32_t* bad, int64_t* qo) {
+  if (!__builtin_isfinite(xv)) *bad |= kErrNonFinite;
+  else if (!(fabs((double)xv) + g.eb2[f] < g.lim[f])) *bad |= kErrRange;
+  int64_t q = quantise(xv, g.m[f], g.inv[f]);
+  if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
+    *bad |= kErrRange;
+    q = 0;
+  }
+  *qo = q;
+  return 0;
+}
+
 __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64_t n, GridDev g,
                                                       const uint32_t* perm_ref,
                                                       const int32_t* q_ref, uint32_t* v_res,
-                                                      int32_t* q_new, uint32_t* err) {
+                                                      int32_t* q_new, uint32_t* err, int vec) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t bad = 0;
-  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
-    uint32_t i = perm_ref[s];
-    for (int f = 0; f < F; f++) {
-      float xv = x.p[f][i];
-      if (!__builtin_isfinite(xv)) bad |= kErrNonFinite;
-      else if (!(fabs((double)xv) + g.eb2[f] < g.lim[f])) bad |= kErrRange;
-      int64_t q = quantise(xv, g.m[f], g.inv[f]);
-      if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
-        bad |= kErrRange;
-        q = 0;
+  if (vec) {  // n % 4 == 0 and 16-byte aligned arrays: 4 slots per thread
+    for (uint64_t s4 = gid; s4 < n / 4; s4 += stride) {
+      const uint4 iv = reinterpret_cast<const uint4*>(perm_ref)[s4];
+      const uint32_t idx[4] = {iv.x, iv.y, iv.z, iv.w};
+      for (int f = 0; f < F; f++) {
+        float xv[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) xv[j] = x.p[f][idx[j]];
+        const int4 qr = reinterpret_cast<const int4*>(q_ref + (uint64_t)f * n)[s4];
+        const int32_t qrv[4] = {qr.x, qr.y, qr.z, qr.w};
+        uint32_t rv[4];
+        int32_t qv[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          int64_t q;
+          t_code(xv[j], g, f, &bad, &q);
+          rv[j] = (uint32_t)zigzag64(q - (int64_t)qrv[j]);
+          qv[j] = (int32_t)q;
+        }
+        reinterpret_cast<uint4*>(v_res + (uint64_t)f * n)[s4] = make_uint4(rv[0], rv[1], rv[2], rv[3]);
+        reinterpret_cast<int4*>(q_new + (uint64_t)f * n)[s4] = make_int4(qv[0], qv[1], qv[2], qv[3]);
       }
-      int64_t r = q - (int64_t)q_ref[(uint64_t)f * n + s];
-      v_res[(uint64_t)f * n + s] = (uint32_t)zigzag64(r);
-      q_new[(uint64_t)f * n + s] = (int32_t)q;
+    }
+  } else {
+    for (uint64_t s = gid; s < n; s += stride) {
+      uint32_t i = perm_ref[s];
+      for (int f = 0; f < F; f++) {
+        int64_t q;
+        t_code(x.p[f][i], g, f, &bad, &q);
+        v_res[(uint64_t)f * n + s] = (uint32_t)zigzag64(q - (int64_t)q_ref[(uint64_t)f * n + s]);
+        q_new[(uint64_t)f * n + s] = (int32_t)q;
+      }
     }
   }
-  bad |= (uint32_t)__shfl_xor((int)bad, 1, kWave);
-  bad |= (uint32_t)__shfl_xor((int)bad, 2, kWave);
-  bad |= (uint32_t)__shfl_xor((int)bad, 4, kWave);
-  bad |= (uint32_t)__shfl_xor((int)bad, 8, kWave);
-  bad |= (uint32_t)__shfl_xor((int)bad, 16, kWave);
-  bad |= (uint32_t)__shfl_xor((int)bad, 32, kWave);
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) bad |= (uint32_t)__shfl_xor((int)bad, d, kWave);
   if (lane_id() == 0 && bad) atomicOr(err, bad);
 }
 
@@ -436,20 +463,47 @@ __global__ __launch_bounds__(kThreads) void k_s_recon(const uint32_t* blk, const
 // LCP-T decode: q = q_ref + residual (residuals decoded as int32 in place).
 __global__ __launch_bounds__(kThreads) void k_t_recon(const int32_t* q_ref, int F, uint64_t n,
                                                       GridDev g, OutPtrs out, int32_t* q_slot,
-                                                      uint32_t* err) {
+                                                      uint32_t* err, int vec) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
-    for (int f = 0; f < F; f++) {
-      const int32_t r = reinterpret_cast<const int32_t*>(out.p[f])[s];
-      int64_t q = (int64_t)q_ref[(uint64_t)f * n + s] + (int64_t)r;
-      if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
-        atomicOr(err, kErrCorrupt);
-        q = 0;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t bad = 0;
+  if (vec) {
+    for (uint64_t s4 = gid; s4 < n / 4; s4 += stride) {
+      for (int f = 0; f < F; f++) {
+        const int4 r = reinterpret_cast<const int4*>(out.p[f])[s4];
+        const int4 qr = reinterpret_cast<const int4*>(q_ref + (uint64_t)f * n)[s4];
+        int64_t q[4] = {(int64_t)qr.x + r.x, (int64_t)qr.y + r.y, (int64_t)qr.z + r.z,
+                        (int64_t)qr.w + r.w};
+        float o[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) {
+          if (q[j] < -(int64_t)kQLimit || q[j] >= (int64_t)kQLimit) {
+            bad = 1;
+            q[j] = 0;
+          }
+          o[j] = reconstruct(q[j], g.eb_q[f], g.m[f]);
+        }
+        reinterpret_cast<float4*>(out.p[f])[s4] = make_float4(o[0], o[1], o[2], o[3]);
+        if (q_slot)
+          reinterpret_cast<int4*>(q_slot + (uint64_t)f * n)[s4] =
+              make_int4((int)q[0], (int)q[1], (int)q[2], (int)q[3]);
       }
-      out.p[f][s] = reconstruct(q, g.eb_q[f], g.m[f]);
-      if (q_slot) q_slot[(uint64_t)f * n + s] = (int32_t)q;
+    }
+  } else {
+    for (uint64_t s = gid; s < n; s += stride) {
+      for (int f = 0; f < F; f++) {
+        const int32_t r = reinterpret_cast<const int32_t*>(out.p[f])[s];
+        int64_t q = (int64_t)q_ref[(uint64_t)f * n + s] + (int64_t)r;
+        if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
+          bad = 1;
+          q = 0;
+        }
+        out.p[f][s] = reconstruct(q, g.eb_q[f], g.m[f]);
+        if (q_slot) q_slot[(uint64_t)f * n + s] = (int32_t)q;
+      }
     }
   }
+  if (bad) atomicOr(err, kErrCorrupt);
 }
 
 // Copies the first min(size, stage) bytes (whole words) of every record into a
@@ -561,12 +615,15 @@ void launch_slot_syms(const FieldPtrs& x, int F, uint64_t n, const GridDev& g, i
                 x, F, n, g, k, perm, v_rel, v_sup, q_slot));
 }
 
+inline bool al16(const void* p) { return ((uintptr_t)p & 15) == 0; }
+
 void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
                     const uint32_t* perm_ref, const int32_t* q_ref, uint32_t* v_res,
                     int32_t* q_new, uint32_t* err, hipStream_t s) {
+  const int vec = (n % 4 == 0) && al16(perm_ref) && al16(q_ref) && al16(v_res) && al16(q_new);
   LCP_TIMED("t_resid", n * (4 + 16ull * F), s,
-            k_t_resid<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(
-                x, F, n, g, perm_ref, q_ref, v_res, q_new, err));
+            k_t_resid<<<grid_for(vec ? n / 4 : n, kThreads * 2, 1u << 16), kThreads, 0, s>>>(
+                x, F, n, g, perm_ref, q_ref, v_res, q_new, err, vec));
 }
 
 void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, uint64_t B,
@@ -586,9 +643,11 @@ void launch_s_recon(const uint32_t* blk, const uint32_t* corner, uint64_t B, int
 
 void launch_t_recon(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,
                     const OutPtrs& out, int32_t* q_slot, uint32_t* err, hipStream_t s) {
+  int vec = (n % 4 == 0) && al16(q_ref) && (!q_slot || al16(q_slot));
+  for (int f = 0; f < F; f++) vec = vec && al16(out.p[f]);
   LCP_TIMED("t_recon", n * (12ull * F + (q_slot ? 4ull * F : 0)), s,
-            k_t_recon<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(
-                q_ref, F, n, g, out, q_slot, err));
+            k_t_recon<<<grid_for(vec ? n / 4 : n, kThreads * 2, 1u << 16), kThreads, 0, s>>>(
+                q_ref, F, n, g, out, q_slot, err, vec));
 }
 
 void launch_gather_headers(const uint64_t* tab, int nrec, int stage, uint8_t* dst, hipStream_t s) {

@@ -89,6 +89,10 @@ struct lcp_plan_s {
   uint32_t* host_small;  // pinned mirror of `small`
   unsigned long long* host_size;
   uint32_t* ext_part;    // extent partials
+  uint32_t* hist_part;   // per-workgroup histograms
+  unsigned long long* hist_max;
+  uint8_t* huff_lens;    // candidate code lengths per (array, halving count)
+  uint32_t* huff_maxd;
   // batched decode staging (pinned host + device mirrors)
   uint8_t *hdr_host, *hdr_dev;
   uint64_t *blobtab_host, *blobtab_dev;
@@ -313,7 +317,8 @@ lcp_status compress_s(lcp_plan_s* P, const float* const* x, uint64_t n, const Ho
     h.eb_q[f] = g[f].eb_q;
   }
   HIP_OK(hipMemsetAsync(P->small + 1, 0, sizeof(uint32_t), s));
-  launch_encode(set, n, P->chunk_log2, P->work, P->chunk_words, P->max_chunks, h, B_dev, out,
+  launch_encode(set, n, P->chunk_log2, P->work, P->chunk_words, P->max_chunks, P->hist_part,
+                P->hist_max, P->huff_lens, P->huff_maxd, h, B_dev, out,
                 cap, P->size_dev, P->small + 1, s);
   res->perm = perm;
   return finish_record(P, &res->size, nullptr, s);
@@ -355,7 +360,8 @@ lcp_status compress_t(lcp_plan_s* P, const float* const* x, uint64_t n, const Re
     h.m[f] = ref.grid[f].m;
     h.eb_q[f] = ref.grid[f].eb_q;
   }
-  launch_encode(set, n, P->chunk_log2, P->work, P->chunk_words, P->max_chunks, h, P->small,
+  launch_encode(set, n, P->chunk_log2, P->work, P->chunk_words, P->max_chunks, P->hist_part,
+                P->hist_max, P->huff_lens, P->huff_maxd, h, P->small,
                 out, cap, P->size_dev, P->small + 1, s);
   uint32_t flags = 0;
   lcp_status st = finish_record(P, size, &flags, s);
@@ -820,6 +826,10 @@ lcp_status alloc_plan(lcp_plan_s* P) {
   A_(P->chunk_words, (uint64_t)kMaxArrays * P->max_chunks + 1);
   A_(P->lut, (uint64_t)(kMaxBatchArrays + 2 * kMaxBatchFrames) << kMaxLen);
   A_(P->ext_part, 2 * kMaxF * 256);
+  A_(P->hist_part, (uint64_t)kMaxArrays * kHistCopies * kAlphabet);
+  A_(P->hist_max, (uint64_t)kMaxArrays * kHistCopies);
+  A_(P->huff_lens, (uint64_t)kMaxArrays * kHuffCandidates * kAlphabet);
+  A_(P->huff_maxd, (uint64_t)kMaxArrays * kHuffCandidates);
   A_(P->hdr_dev, (uint64_t)kHdrStage * kMaxBatchFrames);
   A_(P->blobtab_dev, 2 * kMaxBatchFrames);
   A_(P->arrtab_dev, kMaxBatchArrays + 2 * kMaxBatchFrames);
@@ -839,6 +849,9 @@ lcp_status alloc_plan(lcp_plan_s* P) {
     for (int i = 0; i < 3; i++) A_(P->dqpool[i], (uint64_t)F * N);
   }
 #undef A_
+  if (hipMemset(P->hist_part, 0, sizeof(uint32_t) * kMaxArrays * kHistCopies * kAlphabet) != hipSuccess ||
+      hipMemset(P->hist_max, 0, sizeof(unsigned long long) * kMaxArrays * kHistCopies) != hipSuccess)
+    return LCP_ERR_DEVICE;
   if (hipHostMalloc((void**)&P->host_small, 64 * sizeof(uint32_t), 0) != hipSuccess)
     return LCP_ERR_DEVICE;
   if (hipHostMalloc((void**)&P->host_size, sizeof(unsigned long long), 0) != hipSuccess)

@@ -134,9 +134,18 @@ void launch_gather_headers(const uint64_t* tab, int nrec, int stage, uint8_t* ds
 void launch_copy_perm(const uint32_t* src, uint32_t* dst, uint64_t n, hipStream_t s);
 
 // ---- kernels_codec.hip ----
+// Workgroups per array in the histogram pass; their counts meet in kHistCopies
+// spread copies per array (hist_part: kMaxArrays * kHistCopies * kAlphabet u32,
+// hist_max: kMaxArrays * kHistCopies u64), zero between uses.
+constexpr int kHistBlocks = 1024;
+constexpr int kHistCopies = 32;
+// Candidate halving counts built side by side (huff_lens: kMaxArrays * 32 *
+// kAlphabet bytes, huff_maxd: kMaxArrays * 32 u32).
+constexpr int kHuffCandidates = 32;
 void launch_encode(const ArrSet& set, uint64_t max_n, int chunk_log2, ArrWork* work,
-                   uint32_t* chunk_words, uint64_t max_chunks, const RecHdr& h,
-                   const uint32_t* B_dev, uint8_t* out, uint64_t cap,
+                   uint32_t* chunk_words, uint64_t max_chunks, uint32_t* hist_part,
+                   unsigned long long* hist_max, uint8_t* huff_lens, uint32_t* huff_maxd,
+                   const RecHdr& h, const uint32_t* B_dev, uint8_t* out, uint64_t cap,
                    unsigned long long* size_dev, uint32_t* err, hipStream_t s);
 // Workgroups needed by one array in the Huffman (huff=true) or fixed-length
 // decode launch (0 when the array uses the other coder).
