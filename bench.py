@@ -72,6 +72,20 @@ def cpu_baseline(frames_np, eb_rel, batch, k, n_frames):
                 compress_s=t1 - t0, decompress_s=t2 - t1)
 
 
+def measured_traffic(kernel):
+    """HBM bytes per launch from the committed counter summary, if it was taken on
+    the current kernel sources (else None)."""
+    from paper_2411_00761_amd import profiling
+    path = os.path.join(ROOT, "profiles", f"{kernel}_traffic.json")
+    try:
+        t = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel") != kernel or t.get("source_sha256") != profiling.source_hash():
+        return None
+    return t["traffic_bytes_per_launch"]
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +98,8 @@ def main():
     ap.add_argument("--cpu-frames", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-kernel", default=ROOFLINE_KERNEL)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run three 256 MiB device copies (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -166,6 +182,14 @@ def main():
                   for j in range(3))
     assert max_err <= eb_abs, (max_err, eb_abs)
 
+    if args.copy_probe:
+        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
     ms_per_step = t_total / args.steps * 1e3
     achieved = (kbytes / klaunch) / (kms / klaunch * 1e-3) / 1e9 if klaunch else None
     result = {
@@ -196,7 +220,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": args.roofline_kernel,
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBPS) if achieved else None,
-                     "traffic": None, "launches": klaunch,
+                     "traffic": measured_traffic(args.roofline_kernel), "launches": klaunch,
                      "avg_launch_us": (kms / klaunch * 1e3) if klaunch else None,
                      "bytes_per_launch": (kbytes / klaunch) if klaunch else None},
     }

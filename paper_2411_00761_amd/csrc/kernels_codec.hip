@@ -45,25 +45,10 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
 constexpr int kPrivBins = 256;
 constexpr int kHistVals = 8;  // values per lane per iteration, loads issued together
 
-// Lanes holding the same symbol are grouped by peeling: the first pending lane's
-// symbol is broadcast, its peers found with one ballot, and one of them adds the
-// group size.  The loop runs once per distinct symbol in the wave (a handful for
-// temporal residuals), mostly scalar instructions.
 __device__ inline void hist_group_add(uint32_t* h, uint32_t* hp, uint32_t sym, bool valid,
                                       uint64_t lt) {
   (void)lt;
-  uint64_t todo = __ballot(valid);
-  while (todo) {
-    const int l = __ffsll((long long)todo) - 1;
-    const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)sym, l);
-    const uint64_t m = __ballot(sym == s0) & todo;
-    if (lane_id() == l) {
-      const uint32_t cnt = (uint32_t)__popcll(m);
-      if (s0 < (uint32_t)kPrivBins) hp[s0] += cnt;
-      else atomicAdd(&h[s0], cnt);
-    }
-    todo &= ~m;
-  }
+  wave_hist_add(h, hp, kPrivBins, sym, valid);
 }
 
 __device__ inline int sym_bound(unsigned long long mx) {
@@ -1062,12 +1047,13 @@ void launch_encode(const ArrSet& set, uint64_t max_n, int chunk_log2, ArrWork* w
                    uint32_t* chunk_words, uint64_t max_chunks, uint32_t* hist_part,
                    unsigned long long* hist_max, uint8_t* huff_lens, uint32_t* huff_maxd,
                    const RecHdr& h, const uint32_t* B_dev, uint8_t* out, uint64_t cap,
-                   unsigned long long* size_dev, uint32_t* err, hipStream_t s) {
+                   unsigned long long* size_dev, uint32_t* err, bool hist_done, hipStream_t s) {
   const int A = set.A;
   {
     const int nb = (int)gclamp((max_n + 8191) / 8192, kHistBlocks);
     dim3 g(nb, A);
-    LCP_TIMED("hist", max_n * 4ull * A, s, k_hist<<<g, kThreads, 0, s>>>(set, hist_part, hist_max));
+    if (!hist_done)
+      LCP_TIMED("hist", max_n * 4ull * A, s, k_hist<<<g, kThreads, 0, s>>>(set, hist_part, hist_max));
     k_hist_reduce<<<dim3((kAlphabet + kThreads - 1) / kThreads, A), kThreads, 0, s>>>(
         set, hist_part, hist_max, work);
   }

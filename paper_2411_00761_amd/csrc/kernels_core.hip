@@ -356,13 +356,32 @@ __device__ inline uint32_t t_code(float xv, const GridDev& g, int f, uint32_t* b
   return 0;
 }
 
+// Per-wave private bins of the fused residual histogram (symbols below this).
+constexpr int kResPriv = 256;
+
 __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64_t n, GridDev g,
                                                       const uint32_t* perm_ref,
                                                       const int32_t* q_ref, uint32_t* v_res,
-                                                      int32_t* q_new, uint32_t* err, int vec) {
+                                                      int32_t* q_new, uint32_t* err, int vec,
+                                                      uint32_t* hist_part,
+                                                      unsigned long long* hist_max) {
+  __shared__ uint32_t bins[kMaxF][kThreads / kWave][kResPriv];
+  __shared__ uint32_t smax[kMaxF][kThreads / kWave];
+  for (int j = threadIdx.x; j < F * (kThreads / kWave) * kResPriv; j += kThreads)
+    (&bins[0][0][0])[j] = 0;
+  __syncthreads();
+  const int copy = blockIdx.x % kHistCopies;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint32_t bad = 0;
+  uint32_t rmax[kMaxF];
+#pragma unroll
+  for (int f = 0; f < kMaxF; f++) rmax[f] = 0;
+  auto count = [&](int f, uint32_t r) {
+    uint32_t* shared = hist_part + ((uint64_t)f * kHistCopies + copy) * kAlphabet;
+    int e;
+    wave_hist_add(shared, bins[f][wave_id()], kResPriv, (uint32_t)symbol_of(r, &e), true);
+  };
   if (vec) {  // n % 4 == 0 and 16-byte aligned arrays: 4 slots per thread
     for (uint64_t s4 = gid; s4 < n / 4; s4 += stride) {
       const uint4 iv = reinterpret_cast<const uint4*>(perm_ref)[s4];
@@ -381,9 +400,12 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
           t_code(xv[j], g, f, &bad, &q);
           rv[j] = (uint32_t)zigzag64(q - (int64_t)qrv[j]);
           qv[j] = (int32_t)q;
+          rmax[f] = max(rmax[f], rv[j]);
         }
         reinterpret_cast<uint4*>(v_res + (uint64_t)f * n)[s4] = make_uint4(rv[0], rv[1], rv[2], rv[3]);
         reinterpret_cast<int4*>(q_new + (uint64_t)f * n)[s4] = make_int4(qv[0], qv[1], qv[2], qv[3]);
+#pragma unroll
+        for (int j = 0; j < 4; j++) count(f, rv[j]);
       }
     }
   } else {
@@ -392,14 +414,38 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
       for (int f = 0; f < F; f++) {
         int64_t q;
         t_code(x.p[f][i], g, f, &bad, &q);
-        v_res[(uint64_t)f * n + s] = (uint32_t)zigzag64(q - (int64_t)q_ref[(uint64_t)f * n + s]);
+        const uint32_t r = (uint32_t)zigzag64(q - (int64_t)q_ref[(uint64_t)f * n + s]);
+        v_res[(uint64_t)f * n + s] = r;
         q_new[(uint64_t)f * n + s] = (int32_t)q;
+        rmax[f] = max(rmax[f], r);
+        count(f, r);
       }
     }
   }
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) bad |= (uint32_t)__shfl_xor((int)bad, d, kWave);
   if (lane_id() == 0 && bad) atomicOr(err, bad);
+  for (int f = 0; f < F; f++) {
+    uint32_t m = rmax[f];
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, kWave));
+    if (lane_id() == 0) smax[f][wave_id()] = m;
+  }
+  __syncthreads();
+  // merge the waves' bins into the array's spread copy (non-zero bins only)
+  for (int f = 0; f < F; f++) {
+    uint32_t* shared = hist_part + ((uint64_t)f * kHistCopies + copy) * kAlphabet;
+    for (int j = threadIdx.x; j < kResPriv; j += kThreads) {
+      uint32_t t = 0;
+      for (int w = 0; w < kThreads / kWave; w++) t += bins[f][w][j];
+      if (t) atomicAdd(&shared[j], t);
+    }
+    if (threadIdx.x == 0) {
+      uint32_t m = 0;
+      for (int w = 0; w < kThreads / kWave; w++) m = max(m, smax[f][w]);
+      if (m) atomicMax(&hist_max[(uint64_t)f * kHistCopies + copy], (unsigned long long)m);
+    }
+  }
 }
 
 // ------------------------------------------------------------------ decode side
@@ -619,11 +665,12 @@ inline bool al16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
                     const uint32_t* perm_ref, const int32_t* q_ref, uint32_t* v_res,
-                    int32_t* q_new, uint32_t* err, hipStream_t s) {
+                    int32_t* q_new, uint32_t* err, uint32_t* hist_part,
+                    unsigned long long* hist_max, hipStream_t s) {
   const int vec = (n % 4 == 0) && al16(perm_ref) && al16(q_ref) && al16(v_res) && al16(q_new);
   LCP_TIMED("t_resid", n * (4 + 16ull * F), s,
-            k_t_resid<<<grid_for(vec ? n / 4 : n, kThreads * 2, 1u << 16), kThreads, 0, s>>>(
-                x, F, n, g, perm_ref, q_ref, v_res, q_new, err, vec));
+            k_t_resid<<<grid_for(vec ? n / 4 : n, kThreads * 2, 2048), kThreads, 0, s>>>(
+                x, F, n, g, perm_ref, q_ref, v_res, q_new, err, vec, hist_part, hist_max));
 }
 
 void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, uint64_t B,

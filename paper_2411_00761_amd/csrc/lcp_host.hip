@@ -319,7 +319,7 @@ lcp_status compress_s(lcp_plan_s* P, const float* const* x, uint64_t n, const Ho
   HIP_OK(hipMemsetAsync(P->small + 1, 0, sizeof(uint32_t), s));
   launch_encode(set, n, P->chunk_log2, P->work, P->chunk_words, P->max_chunks, P->hist_part,
                 P->hist_max, P->huff_lens, P->huff_maxd, h, B_dev, out,
-                cap, P->size_dev, P->small + 1, s);
+                cap, P->size_dev, P->small + 1, false, s);
   res->perm = perm;
   return finish_record(P, &res->size, nullptr, s);
 }
@@ -341,7 +341,7 @@ lcp_status compress_t(lcp_plan_s* P, const float* const* x, uint64_t n, const Re
   }
   launch_fill_u32(P->small + 1, 1, 0u, s);
   launch_t_resid(fp, F, n, gd, P->ppool[ref.perm], P->qpool[ref.q], P->v_slot, q_new,
-                 P->small + 1, s);
+                 P->small + 1, P->hist_part, P->hist_max, s);
   ArrSet set;
   memset(&set, 0, sizeof(set));
   set.A = F;
@@ -362,7 +362,7 @@ lcp_status compress_t(lcp_plan_s* P, const float* const* x, uint64_t n, const Re
   }
   launch_encode(set, n, P->chunk_log2, P->work, P->chunk_words, P->max_chunks, P->hist_part,
                 P->hist_max, P->huff_lens, P->huff_maxd, h, P->small,
-                out, cap, P->size_dev, P->small + 1, s);
+                out, cap, P->size_dev, P->small + 1, true, s);
   uint32_t flags = 0;
   lcp_status st = finish_record(P, size, &flags, s);
   if (flags & kErrNonFinite) return LCP_ERR_ARG;

@@ -113,9 +113,12 @@ void launch_slot_syms(const FieldPtrs& x, int F, uint64_t n, const GridDev& g, i
                       hipStream_t s);
 // LCP-T residuals; err gets kErrNonFinite / kErrRange when the frame cannot be
 // coded on the reference grid.
+// The residual symbols of field f are also counted into array f's spread
+// histogram copies (hist_part / hist_max, as launch_encode expects them).
 void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
                     const uint32_t* perm_ref, const int32_t* q_ref, uint32_t* v_res,
-                    int32_t* q_new, uint32_t* err, hipStream_t s);
+                    int32_t* q_new, uint32_t* err, uint32_t* hist_part,
+                    unsigned long long* hist_max, hipStream_t s);
 void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, uint64_t B,
                      uint64_t n, uint64_t total_blocks, const uint32_t* bn, int k,
                      uint32_t* corner, uint32_t* mark, uint32_t* err, hipStream_t s);
@@ -146,7 +149,7 @@ void launch_encode(const ArrSet& set, uint64_t max_n, int chunk_log2, ArrWork* w
                    uint32_t* chunk_words, uint64_t max_chunks, uint32_t* hist_part,
                    unsigned long long* hist_max, uint8_t* huff_lens, uint32_t* huff_maxd,
                    const RecHdr& h, const uint32_t* B_dev, uint8_t* out, uint64_t cap,
-                   unsigned long long* size_dev, uint32_t* err, hipStream_t s);
+                   unsigned long long* size_dev, uint32_t* err, bool hist_done, hipStream_t s);
 // Workgroups needed by one array in the Huffman (huff=true) or fixed-length
 // decode launch (0 when the array uses the other coder).
 uint32_t decode_blocks(const DecArr& d, int chunk_log2, bool huff);
