@@ -72,6 +72,107 @@ def cpu_baseline(frames_np, eb_rel, batch, k, n_frames):
                 compress_s=t1 - t0, decompress_s=t2 - t1)
 
 
+def bench_batched(args, torch, lcp, datagen, dev):
+    """Independent frames of uneven size: one batched lcp_compress / lcp_decompress
+    call for all of them against one call per frame (the plain form), same plan
+    parameters, same bytes."""
+    xs = datagen.batched_frames(args.batched_frames, 14, 22, seed=4)
+    sizes = [x.shape[1] for x in xs]
+    ntot = int(sum(sizes))
+    frames = [torch.from_numpy(x).to(dev) for x in xs]
+    del xs
+    torch.cuda.synchronize()
+    size_d = 12 * ntot
+    big = int(np.argmax(sizes))
+    bplan = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, block_log2=-1, sample=frames[big],
+                     max_particles=max(sizes), max_batch_particles=ntot,
+                     max_batch_frames=len(frames))
+    k = bplan.block_log2
+    pplan = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, block_log2=k, max_particles=max(sizes),
+                     max_batch_frames=1)
+    cap = sum((bplan.bound(n) + 3) & ~3 for n in sizes)
+    outb = torch.empty(cap, dtype=torch.uint8, device=dev)
+    outp = torch.empty(cap, dtype=torch.uint8, device=dev)
+    decb = [torch.empty((3, n), dtype=torch.float32, device=dev) for n in sizes]
+
+    def batched():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, offs, _, _ = bplan.compress(frames, out=outb)
+        t1 = time.perf_counter()
+        bplan.decompress(outb, offs, outs=decb)
+        torch.cuda.synchronize()
+        return t1 - t0, time.perf_counter() - t1, offs
+
+    def plain():
+        torch.cuda.synchronize()
+        offs, lat_c, lat_d = [0], [], []
+        for f in frames:
+            t = time.perf_counter()
+            _, o, _, _ = pplan.compress([f], out=outp[offs[-1]:])
+            lat_c.append(time.perf_counter() - t)
+            offs.append(offs[-1] + o[1])
+        for j in range(len(frames)):
+            t = time.perf_counter()
+            pplan.decompress(outp, offs[j:j + 2], outs=[decb[j]])
+            torch.cuda.synchronize()
+            lat_d.append(time.perf_counter() - t)
+        return sum(lat_c), sum(lat_d), offs, lat_c, lat_d
+
+    for _ in range(args.batched_warmup):
+        batched()
+        plain()
+    bc = bd = pc = pd = 0.0
+    lc_all, ld_all, batch_lat = [], [], []
+    for _ in range(args.batched_steps):
+        c, d, boffs = batched()
+        bc += c
+        bd += d
+        batch_lat.append(c + d)
+        c, d, poffs, lc, ld = plain()
+        pc += c
+        pd += d
+        lc_all += lc
+        ld_all += ld
+    torch.cuda.synchronize()
+    same = boffs == poffs and torch.equal(outb[:boffs[-1]], outp[:poffs[-1]])
+    assert same, "batched records differ from per-frame records"
+    # error bound on a few frames, against the slot permutation
+    chk = [0, 1, big, int(np.argmin(sizes))]
+    cplan = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, block_log2=k, max_particles=max(sizes),
+                     max_batch_particles=ntot, max_batch_frames=len(chk))
+    out2, offs2, _, perms = cplan.compress([frames[j] for j in chk], want_perm=True)
+    dec = cplan.decompress(out2, offs2)
+    max_ratio_err = 0.0
+    for i, j in enumerate(chk):
+        f = frames[j]
+        eb_abs = args.eb * (float(f.max()) - float(f.min()))
+        err = float((dec[i].double() - f[:, perms[i].long()].double()).abs().max())
+        assert err <= eb_abs, (j, err, eb_abs)
+        max_ratio_err = max(max_ratio_err, err / eb_abs)
+    steps = args.batched_steps
+    pct = lambda v, q: float(np.percentile(np.asarray(v) * 1e3, q))  # noqa: E731
+    return {
+        "workload": f"{len(frames)} independent frames, n log-uniform in [2^14, 2^22] "
+                    f"(total {ntot}), even uniform / odd clustered in [0,100)^3, float32 xyz, "
+                    f"eb={args.eb:g} x each frame's range, LCP-S, block_log2 {k}",
+        "frames": len(frames), "particles": ntot,
+        "batched_compress_GBps": size_d * steps / bc / 1e9,
+        "batched_decompress_GBps": size_d * steps / bd / 1e9,
+        "batched_GBps": size_d * steps / (bc + bd) / 1e9,
+        "plain_compress_GBps": size_d * steps / pc / 1e9,
+        "plain_decompress_GBps": size_d * steps / pd / 1e9,
+        "plain_GBps": size_d * steps / (pc + pd) / 1e9,
+        "speedup_vs_plain": (pc + pd) / (bc + bd),
+        "batch_latency_ms_p50": pct(batch_lat, 50),
+        "plain_compress_call_ms_p50": pct(lc_all, 50), "plain_compress_call_ms_p99": pct(lc_all, 99),
+        "plain_decompress_call_ms_p50": pct(ld_all, 50),
+        "plain_decompress_call_ms_p99": pct(ld_all, 99),
+        "ratio": size_d / boffs[-1], "bytes_equal_plain": bool(same),
+        "max_err_over_eb": max_ratio_err, "steps": steps,
+    }
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch from the committed counter summary, if it was taken on
     the current kernel sources (else None)."""
@@ -100,6 +201,11 @@ def main():
     ap.add_argument("--roofline-kernel", default=ROOFLINE_KERNEL)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run three 256 MiB device copies (counter calibration)")
+    ap.add_argument("--workloads", default="md,batched",
+                    help="comma list: md (the trajectory, the headline value), batched")
+    ap.add_argument("--batched-frames", type=int, default=256)
+    ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--batched-warmup", type=int, default=1)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -174,12 +280,13 @@ def main():
     eb_abs = args.eb * (float(frames[0].max()) - float(frames[0].min()))
     chk = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=args.batch, block_log2=k,
                    max_particles=args.n)
-    out2, offs2, _, perms = chk.compress(frames[:3], want_perm=True)
+    nchk = min(3, len(frames))
+    out2, offs2, _, perms = chk.compress(frames[:nchk], want_perm=True)
     dchk = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=args.batch,
                     block_log2=k, max_particles=args.n)
     dec = dchk.decompress(out2, offs2)
     max_err = max(float((dec[j].double() - frames[j][:, perms[j].long()].double()).abs().max())
-                  for j in range(3))
+                  for j in range(nchk))
     assert max_err <= eb_abs, (max_err, eb_abs)
 
     if args.copy_probe:
@@ -224,6 +331,12 @@ def main():
                      "avg_launch_us": (kms / klaunch * 1e3) if klaunch else None,
                      "bytes_per_launch": (kbytes / klaunch) if klaunch else None},
     }
+    if "batched" in args.workloads.split(","):
+        del frames, decbufs, outbuf, plan, dplan
+        torch.cuda.empty_cache()
+        log("batched workload")
+        result["batched"] = bench_batched(args, torch, lcp, datagen, dev)
+        log(json.dumps(result["batched"]))
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_frames} frames")
         cb = cpu_baseline(frames_np, args.eb, args.batch, k, args.cpu_frames)

@@ -80,6 +80,11 @@ typedef struct {
   uint64_t hbm_budget_bytes; /* 0 = unlimited; otherwise lcp_plan fails with
                                 LCP_ERR_BUDGET if its scratch would exceed it */
   int device;                /* HIP device ordinal */
+  uint64_t max_batch_particles; /* single-frame plans: most particles in one batch of
+                                   independent frames, max_particles..2^32-1
+                                   (0 = max_particles) */
+  int max_batch_frames;         /* single-frame plans: most frames in one batch, at most
+                                   1024 (0 = 64) */
 } lcp_params;
 
 typedef struct lcp_plan_s* lcp_plan_t;
@@ -134,7 +139,11 @@ uint64_t lcp_bound(lcp_plan_t plan, uint64_t n);
  * methods_used (host, nullable): LCP_METHOD_S or LCP_METHOD_T per frame.
  * perms (nullable; else n_frames device pointers, each nullable): receives the
  * slot -> input index permutation of each frame (n uint32 values).
- * In single-frame plans (multi_frame == 0) the frames are independent.
+ * In single-frame plans (multi_frame == 0) the frames are independent, and
+ * consecutive frames are compressed together, as many at a time as the plan's
+ * max_batch_frames and max_batch_particles allow: one extent pass, one sort and
+ * one set of coding launches per batch (the records are the same bytes as when
+ * the frames are compressed one per call).
  * Errors: LCP_ERR_ARG, LCP_ERR_EB_TOO_SMALL, LCP_ERR_RANGE, LCP_ERR_CAPACITY
  * (out_offsets[n_frames] then holds the bytes required so far), LCP_ERR_DEVICE,
  * LCP_ERR_NO_REFERENCE (LCP_METHOD_T without a resident reference). */

@@ -31,6 +31,17 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// Array of workgroup b: the largest a < A with prefix[a] <= b.
+__device__ inline uint32_t array_of_block(const uint32_t* prefix, int A, uint32_t b) {
+  int lo = 0, hi = A - 1;  // largest a with prefix[a] <= b
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (prefix[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return (uint32_t)lo;
+}
+
 // ------------------------------------------------------------------ histogram
 // Each workgroup counts its share of one array in LDS and writes the whole
 // histogram as a partial (coalesced); a second kernel sums the partials per bin.
@@ -56,12 +67,15 @@ __device__ inline int sym_bound(unsigned long long mx) {
   return symbol_of(mx, &e);
 }
 
-__global__ __launch_bounds__(kThreads) void k_hist(ArrSet set, uint32_t* part,
-                                                   unsigned long long* part_max) {
+__global__ __launch_bounds__(kThreads) void k_hist(const EncArr* E, const uint32_t* pre, int NA,
+                                                   uint32_t* part, unsigned long long* part_max) {
   __shared__ uint32_t h[kAlphabet];
   __shared__ uint32_t hpriv[kThreads / kWave][kPrivBins];
   __shared__ unsigned long long smax[kThreads / kWave];
-  const ArrIn a = set.a[blockIdx.y];
+  const uint32_t ai = array_of_block(pre, NA, blockIdx.x);
+  const EncArr& e = E[ai];
+  const uint32_t lb = blockIdx.x - pre[ai], nb = pre[ai + 1] - pre[ai];
+  const ArrIn a = e.in;
   const uint64_t n = arr_len(a);
   for (int j = threadIdx.x; j < kAlphabet; j += kThreads) h[j] = 0;
   for (int j = threadIdx.x; j < kPrivBins * (kThreads / kWave); j += kThreads) (&hpriv[0][0])[j] = 0;
@@ -69,8 +83,8 @@ __global__ __launch_bounds__(kThreads) void k_hist(ArrSet set, uint32_t* part,
   uint32_t* hp = hpriv[wave_id()];
   uint64_t mx = 0;
   const uint64_t lt = lanemask_lt();
-  const uint64_t stride = (uint64_t)gridDim.x * kThreads * kHistVals;
-  for (uint64_t base = ((uint64_t)blockIdx.x * kThreads + wave_id() * kWave) * kHistVals; base < n;
+  const uint64_t stride = (uint64_t)nb * kThreads * kHistVals;
+  for (uint64_t base = ((uint64_t)lb * kThreads + wave_id() * kWave) * kHistVals; base < n;
        base += stride) {
     uint64_t v[kHistVals];
 #pragma unroll
@@ -80,9 +94,9 @@ __global__ __launch_bounds__(kThreads) void k_hist(ArrSet set, uint32_t* part,
     }
 #pragma unroll
     for (int j = 0; j < kHistVals; j++) {
-      int e;
+      int ex;
       const bool valid = base + (uint64_t)j * kWave + lane_id() < n;
-      hist_group_add(h, hp, (uint32_t)symbol_of(v[j], &e), valid, lt);
+      hist_group_add(h, hp, (uint32_t)symbol_of(v[j], &ex), valid, lt);
       mx = v[j] > mx ? v[j] : mx;
     }
   }
@@ -96,32 +110,31 @@ __global__ __launch_bounds__(kThreads) void k_hist(ArrSet set, uint32_t* part,
   unsigned long long bm = 0;
   for (int w = 0; w < kThreads / kWave; w++) bm = smax[w] > bm ? smax[w] : bm;
   const int top = sym_bound(bm);
-  // add the non-zero bins into one of kHistCopies spread copies of the array's
-  // histogram (few workgroups share an address, so the atomics do not queue)
-  const int copy = blockIdx.x % kHistCopies;
-  uint32_t* dst = part + ((uint64_t)blockIdx.y * kHistCopies + copy) * kAlphabet;
+  // add the non-zero bins into one of the array's spread copies (few
+  // workgroups share an address, so the atomics do not queue)
+  const uint32_t copy = e.copy0 + lb % e.copies;
+  uint32_t* dst = part + (uint64_t)copy * kAlphabet;
   for (int j = threadIdx.x; j <= top; j += kThreads) {
     uint32_t t = h[j];
     if (j < kPrivBins)
       for (int w = 0; w < kThreads / kWave; w++) t += hpriv[w][j];
     if (t) atomicAdd(&dst[j], t);
   }
-  if (threadIdx.x == 0 && bm)
-    atomicMax(&part_max[(uint64_t)blockIdx.y * kHistCopies + copy], bm);
+  if (threadIdx.x == 0 && bm) atomicMax(&part_max[copy], bm);
 }
 
 // Sums the spread copies per bin and clears them for the next use.
-__global__ __launch_bounds__(kThreads) void k_hist_reduce(ArrSet set, uint32_t* part,
+__global__ __launch_bounds__(kThreads) void k_hist_reduce(const EncArr* E, uint32_t* part,
                                                           unsigned long long* part_max,
                                                           ArrWork* W) {
   const int a = blockIdx.y;
+  const EncArr& e = E[a];
   ArrWork& w = W[a];
-  uint32_t* src = part + (uint64_t)a * kHistCopies * kAlphabet;
+  uint32_t* src = part + (uint64_t)e.copy0 * kAlphabet;
   const int j = blockIdx.x * kThreads + threadIdx.x;
   if (j < kAlphabet) {
     uint32_t t = 0;
-#pragma unroll
-    for (int c = 0; c < kHistCopies; c++) {
+    for (uint32_t c = 0; c < e.copies; c++) {
       t += src[(uint64_t)c * kAlphabet + j];
       src[(uint64_t)c * kAlphabet + j] = 0;
     }
@@ -129,13 +142,13 @@ __global__ __launch_bounds__(kThreads) void k_hist_reduce(ArrSet set, uint32_t* 
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     unsigned long long m = 0;
-    for (int c = 0; c < kHistCopies; c++) {
-      unsigned long long v = part_max[(uint64_t)a * kHistCopies + c];
+    for (uint32_t c = 0; c < e.copies; c++) {
+      unsigned long long v = part_max[e.copy0 + c];
       m = v > m ? v : m;
-      part_max[(uint64_t)a * kHistCopies + c] = 0;
+      part_max[e.copy0 + c] = 0;
     }
     w.maxv = m;
-    w.n = (uint32_t)arr_len(set.a[a]);
+    w.n = (uint32_t)arr_len(e.in);
   }
 }
 
@@ -173,7 +186,7 @@ __device__ inline uint32_t block_max_u32(uint32_t v, uint32_t* misc) {
 constexpr int kHalvings = 32;  // counts < 2^31: after 31 halvings every count is 1
 
 __global__ __launch_bounds__(kHT) void k_huff_lengths(const ArrWork* W, uint8_t* lens_all,
-                                                      uint32_t* maxd_all) {
+                                                      uint32_t* maxd_all, int h0, int gate) {
   __shared__ uint64_t sm64[8192];
   uint8_t* smb = reinterpret_cast<uint8_t*>(sm64);
   uint32_t* leafw = reinterpret_cast<uint32_t*>(smb);
@@ -184,7 +197,9 @@ __global__ __launch_bounds__(kHT) void k_huff_lengths(const ArrWork* W, uint8_t*
   uint16_t* parent = reinterpret_cast<uint16_t*>(smb + kOffParent);
   uint32_t* misc = reinterpret_cast<uint32_t*>(smb + kOffMisc);
 
-  const int a = blockIdx.x, halvings = blockIdx.y;
+  const int a = blockIdx.x, halvings = blockIdx.y + h0;
+  // gate: halvings are only needed when the plain build is too deep
+  if (gate && maxd_all[(uint64_t)a * kHalvings] <= (uint32_t)kMaxLen) return;
   const ArrWork& w = W[a];
   const int t = threadIdx.x;
   uint8_t* lens = lens_all + ((uint64_t)a * kHalvings + halvings) * kAlphabet;
@@ -378,9 +393,14 @@ __global__ __launch_bounds__(kHT) void k_huff_codes(ArrWork* W, const uint8_t* l
     }
     return;
   }
+  // the first (fewest halvings) build that fits; 31 halvings always fit, and
+  // candidates past the first fit may not have been built
   int hsel = kHalvings - 1;
-  for (int h = kHalvings - 1; h >= 0; h--)
-    if (maxd_all[(uint64_t)a * kHalvings + h] <= (uint32_t)kMaxLen) hsel = h;
+  for (int h = 0; h < kHalvings - 1; h++)
+    if (maxd_all[(uint64_t)a * kHalvings + h] <= (uint32_t)kMaxLen) {
+      hsel = h;
+      break;
+    }
   const uint8_t* src = lens_all + ((uint64_t)a * kHalvings + hsel) * kAlphabet;
   for (int s = t; s < kAlphabet; s += kHT) lens[s] = src[s];
   uint32_t* blc = misc;        // [16] code-length counts
@@ -477,22 +497,24 @@ __device__ inline uint32_t run_bits(const ArrIn& in, const ArrWork& w, const uin
 }
 
 template <int RUN>
-__global__ __launch_bounds__(kThreads) void k_chunk_bits(ArrSet set, const ArrWork* W,
-                                                         int chunk_log2, uint32_t* cw,
-                                                         uint64_t max_chunks) {
+__global__ __launch_bounds__(kThreads) void k_chunk_bits(const EncArr* E, const ArrWork* W,
+                                                         const uint32_t* pre, int NA,
+                                                         int chunk_log2, uint32_t* cw) {
   __shared__ uint32_t sm[kThreads / kWave];
   __shared__ uint32_t lc_lds[kPrivBins];
-  const int a = blockIdx.y;
-  const ArrIn in = set.a[a];
+  const uint32_t a = array_of_block(pre, NA, blockIdx.x);
+  const uint32_t lb = blockIdx.x - pre[a], nb = pre[a + 1] - pre[a];
+  const ArrIn in = E[a].in;
   const ArrWork& w = W[a];
   const uint64_t n = w.n;
   const uint64_t C = 1ull << chunk_log2;
   const uint64_t nchunks = (n + C - 1) >> chunk_log2;
-  if (w.U == 0 || blockIdx.x >= nchunks) return;
+  if (w.U == 0 || lb >= nchunks) return;
   load_codes(w, lc_lds);
   __syncthreads();
+  uint32_t* cwa = cw + E[a].cw0;
   const uint64_t run = C >= (uint64_t)kThreads ? C / kThreads : 1;
-  for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+  for (uint64_t c = lb; c < nchunks; c += nb) {
     const uint64_t cend = min(n, (c + 1) * C);
     const uint64_t i0 = min(cend, c * C + threadIdx.x * run);
     const uint64_t i1 = min(cend, i0 + run);
@@ -500,21 +522,20 @@ __global__ __launch_bounds__(kThreads) void k_chunk_bits(ArrSet set, const ArrWo
     uint32_t bits = wave_sum(run_bits<RUN>(in, w, lc_lds, i0, i1, vals));
     if (lane_id() == 0) sm[wave_id()] = bits;
     __syncthreads();
-    if (threadIdx.x == 0)
-      cw[(uint64_t)a * max_chunks + c] = (sm[0] + sm[1] + sm[2] + sm[3] + 31u) >> 5;
+    if (threadIdx.x == 0) cwa[c] = (sm[0] + sm[1] + sm[2] + sm[3] + 31u) >> 5;
     __syncthreads();
   }
 }
 
 // Inclusive scan of one array's chunk word counts (one workgroup per array).
-__global__ __launch_bounds__(kHT) void k_chunk_scan(ArrWork* W, int chunk_log2, uint32_t* cw,
-                                                    uint64_t max_chunks) {
+__global__ __launch_bounds__(kHT) void k_chunk_scan(const EncArr* E, ArrWork* W, int chunk_log2,
+                                                    uint32_t* cw) {
   __shared__ uint32_t sm[kHT / kWave + 1];
   const int a = blockIdx.x;
   ArrWork& w = W[a];
   const uint64_t n = w.n;
   const uint64_t nchunks = (n + (1ull << chunk_log2) - 1) >> chunk_log2;
-  uint32_t* p = cw + (uint64_t)a * max_chunks;
+  uint32_t* p = cw + E[a].cw0;
   uint64_t carry = 0;
   if (w.U != 0) {
     for (uint64_t base = 0; base < nchunks; base += (uint64_t)kHT * 4) {
@@ -553,39 +574,21 @@ __device__ inline void put64(uint8_t* base, uint64_t off, uint64_t v) {
 }
 
 // Chooses each array's coder (the shorter; a tie keeps fixed length), places
-// the arrays and writes header, grids and directory.
-__global__ void k_layout(ArrWork* W, RecHdr h, const uint32_t* B_dev, uint8_t* out,
-                         uint64_t cap, unsigned long long* size_dev, uint32_t* err) {
-  if (threadIdx.x != 0) return;
+// the arrays, sizes the records and places them back to back (one thread per
+// record, workgroup scan of the sizes), then writes headers, grids and
+// directories.  Every record size is a multiple of 4 bytes.
+__device__ inline void write_header(const EncRec& rc, const ArrWork* W, uint8_t* out) {
+  const RecHdr& h = rc.h;
   const int A = h.A;
-  uint64_t off = (uint64_t)kHdrBytes + 8ull * h.F + (uint64_t)kDirBytes * A;
-  const uint64_t hdr = off;
-  for (int a = 0; a < A; a++) {
-    ArrWork& w = W[a];
-    uint64_t n = w.n;
-    int wd = bitwidth64(w.maxv);
-    uint64_t fixed = 4 * ((n * (uint64_t)wd + 31) / 32);
-    uint64_t huff = 4ull * w.U + 4ull * w.nchunks + 4ull * w.huff_words;
-    bool use_h = w.U != 0 && huff < fixed;
-    w.coder = use_h ? 1u : 0u;
-    w.w = (uint32_t)wd;
-    w.nbytes = use_h ? huff : fixed;
-    w.off = off;
-    off += w.nbytes;
-  }
-  *size_dev = off;
-  if (off > cap) {
-    atomicOr(err, kErrCapacity);
-    return;
-  }
+  const uint64_t hdr = (uint64_t)kHdrBytes + 8ull * h.F + (uint64_t)kDirBytes * A;
   for (uint64_t o = 0; o < hdr; o += 4) put32(out, o, 0u);
   put32(out, 0, kMagic);
   put32(out, 4, (uint32_t)kVersion | ((uint32_t)h.mode << 16) | ((uint32_t)h.F << 24));
   put32(out, 8, (uint32_t)h.k | ((uint32_t)h.chunk_log2 << 8) | ((uint32_t)A << 16));
   put32(out, 12, (uint32_t)hdr);
   put64(out, 16, h.n);
-  put64(out, 24, h.mode == 0 ? (uint64_t)*B_dev : 0ull);
-  put64(out, 32, off);
+  put64(out, 24, h.mode == 0 ? (uint64_t)*rc.B_dev : 0ull);
+  put64(out, 32, rc.size);
   for (int d = 0; d < 3; d++) put32(out, 40 + 4 * d, h.bn[d]);
   put64(out, 56, h.seq);
   put64(out, 64, h.ref_seq);
@@ -594,7 +597,7 @@ __global__ void k_layout(ArrWork* W, RecHdr h, const uint32_t* B_dev, uint8_t* o
     put32(out, kHdrBytes + 8 * f + 4, __float_as_uint(h.eb_q[f]));
   }
   for (int a = 0; a < A; a++) {
-    const ArrWork& w = W[a];
+    const ArrWork& w = W[rc.a0 + a];
     uint64_t d = (uint64_t)kHdrBytes + 8ull * h.F + (uint64_t)kDirBytes * a;
     uint32_t param = w.coder ? w.L : w.w;
     put32(out, d, w.coder | (param << 8));
@@ -605,18 +608,65 @@ __global__ void k_layout(ArrWork* W, RecHdr h, const uint32_t* B_dev, uint8_t* o
   }
 }
 
+__global__ __launch_bounds__(kHT) void k_layout(ArrWork* W, EncRec* recs, int R, uint8_t* out,
+                                                uint64_t cap, unsigned long long* offs,
+                                                uint32_t* err) {
+  __shared__ unsigned long long sm[kHT / kWave + 1];
+  unsigned long long carry = 0;
+  for (int base = 0; base < R; base += kHT) {
+    const int r = base + (int)threadIdx.x;
+    unsigned long long size = 0;
+    if (r < R) {
+      EncRec& rc = recs[r];
+      const int A = rc.h.A;
+      uint64_t off = (uint64_t)kHdrBytes + 8ull * rc.h.F + (uint64_t)kDirBytes * A;
+      for (int a = 0; a < A; a++) {
+        ArrWork& w = W[rc.a0 + a];
+        uint64_t n = w.n;
+        int wd = bitwidth64(w.maxv);
+        uint64_t fixed = 4 * ((n * (uint64_t)wd + 31) / 32);
+        uint64_t huff = 4ull * w.U + 4ull * w.nchunks + 4ull * w.huff_words;
+        bool use_h = w.U != 0 && huff < fixed;
+        w.coder = use_h ? 1u : 0u;
+        w.w = (uint32_t)wd;
+        w.nbytes = use_h ? huff : fixed;
+        w.off = off;
+        off += w.nbytes;
+      }
+      size = off;
+      rc.size = off;
+    }
+    unsigned long long tot;
+    const unsigned long long incl = block_incl_scan(size, sm, &tot);
+    if (r < R) {
+      recs[r].off = carry + incl - size;
+      offs[r] = carry + incl - size;
+    }
+    carry += tot;
+  }
+  if (threadIdx.x == 0) offs[R] = carry;
+  if (carry > cap) {
+    if (threadIdx.x == 0) atomicOr(err, kErrCapacity);
+    return;
+  }
+  for (int r = threadIdx.x; r < R; r += kHT) write_header(recs[r], W, out + recs[r].off);
+}
+
 // ------------------------------------------------------------------ packing
-__global__ __launch_bounds__(kThreads) void k_pack_fixed(ArrSet set, const ArrWork* W,
-                                                         uint8_t* out, const uint32_t* err) {
-  const int a = blockIdx.y;
+__global__ __launch_bounds__(kThreads) void k_pack_fixed(const EncArr* E, const ArrWork* W,
+                                                         const EncRec* recs, const uint32_t* pre,
+                                                         int NA, uint8_t* out,
+                                                         const uint32_t* err) {
+  const uint32_t a = array_of_block(pre, NA, blockIdx.x);
+  const uint32_t lb = blockIdx.x - pre[a], nb = pre[a + 1] - pre[a];
   const ArrWork& w = W[a];
   if (w.coder != 0 || w.w == 0 || (*err & kErrCapacity)) return;
-  const ArrIn in = set.a[a];
+  const ArrIn in = E[a].in;
   const uint64_t n = w.n, wd = w.w;
   const uint64_t nwords = (n * wd + 31) / 32;
-  uint32_t* dst = reinterpret_cast<uint32_t*>(out + w.off);
-  const uint64_t stride = (uint64_t)gridDim.x * kThreads;
-  for (uint64_t j = (uint64_t)blockIdx.x * kThreads + threadIdx.x; j < nwords; j += stride) {
+  uint32_t* dst = reinterpret_cast<uint32_t*>(out + recs[E[a].rec].off + w.off);
+  const uint64_t stride = (uint64_t)nb * kThreads;
+  for (uint64_t j = (uint64_t)lb * kThreads + threadIdx.x; j < nwords; j += stride) {
     const uint64_t bit0 = 32 * j;
     const uint64_t i0 = bit0 / wd;
     uint64_t i1 = (bit0 + 31) / wd;
@@ -627,9 +677,9 @@ __global__ __launch_bounds__(kThreads) void k_pack_fixed(ArrSet set, const ArrWo
       const uint64_t lo = pos > bit0 ? pos : bit0;
       const uint64_t hi = min(pos + wd, bit0 + 32);
       if (lo >= hi) continue;
-      const uint64_t nb = hi - lo;
+      const uint64_t nbits = hi - lo;
       const uint64_t v = arr_load(in, i);
-      const uint64_t part = (v >> (pos + wd - hi)) & (nb >= 32 ? 0xFFFFFFFFull : ((1ull << nb) - 1));
+      const uint64_t part = (v >> (pos + wd - hi)) & (nbits >= 32 ? 0xFFFFFFFFull : ((1ull << nbits) - 1));
       word |= (uint32_t)(part << (bit0 + 32 - hi));
     }
     dst[j] = word;
@@ -664,31 +714,33 @@ struct BitSink {
 // symbols, starting at the bit offset given by a block prefix scan of the runs'
 // lengths, into the chunk's image in LDS, which is then written out coalesced.
 template <int RUN>
-__global__ __launch_bounds__(kThreads) void k_pack_huff(ArrSet set, const ArrWork* W,
-                                                        int chunk_log2, const uint32_t* cw,
-                                                        uint64_t max_chunks, uint32_t max_words,
-                                                        uint8_t* out, const uint32_t* err) {
+__global__ __launch_bounds__(kThreads) void k_pack_huff(const EncArr* E, const ArrWork* W,
+                                                        const EncRec* recs, const uint32_t* pre,
+                                                        int NA, int chunk_log2, const uint32_t* cw,
+                                                        uint32_t max_words, uint8_t* out,
+                                                        const uint32_t* err) {
   extern __shared__ uint32_t buf[];
   __shared__ uint32_t sm[kThreads / kWave + 1];
   __shared__ uint32_t lc_lds[kPrivBins];
-  const int a = blockIdx.y;
+  const uint32_t a = array_of_block(pre, NA, blockIdx.x);
+  const uint32_t lb = blockIdx.x - pre[a], nb = pre[a + 1] - pre[a];
   const ArrWork& w = W[a];
   if (w.coder != 1 || (*err & kErrCapacity)) return;
   load_codes(w, lc_lds);
   __syncthreads();
-  const ArrIn in = set.a[a];
+  const ArrIn in = E[a].in;
   const uint64_t n = w.n, nchunks = w.nchunks, U = w.U;
-  uint32_t* tab = reinterpret_cast<uint32_t*>(out + w.off);
+  uint32_t* tab = reinterpret_cast<uint32_t*>(out + recs[E[a].rec].off + w.off);
   uint32_t* offs = tab + U;
   uint32_t* payload = offs + nchunks;
-  const uint32_t* ce = cw + (uint64_t)a * max_chunks;
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t gstride = (uint64_t)gridDim.x * blockDim.x;
+  const uint32_t* ce = cw + E[a].cw0;
+  const uint64_t gid = (uint64_t)lb * blockDim.x + threadIdx.x;
+  const uint64_t gstride = (uint64_t)nb * blockDim.x;
   for (uint64_t j = gid; j < U; j += gstride) tab[j] = w.table[j];
   for (uint64_t c = gid; c < nchunks; c += gstride) offs[c] = ce[c];
   const uint64_t C = 1ull << chunk_log2;
   const uint64_t run = C >= (uint64_t)kThreads ? C / kThreads : 1;
-  for (uint64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+  for (uint64_t c = lb; c < nchunks; c += nb) {
     const uint32_t wbeg = c ? ce[c - 1] : 0u;
     const uint32_t nw = ce[c] - wbeg;
     const bool fits = nw <= max_words;
@@ -734,19 +786,17 @@ __global__ __launch_bounds__(kThreads) void k_pack_huff(ArrSet set, const ArrWor
 // workgroup counts (binary search), so one launch decodes all arrays of all
 // frames: the entropy decoding of a batch does not depend on the reference
 // chain, only the reconstruction that follows does.
-__device__ inline uint32_t array_of_block(const uint32_t* prefix, int A, uint32_t b) {
-  int lo = 0, hi = A - 1;  // largest a with prefix[a] <= b
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (prefix[mid] <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  return (uint32_t)lo;
-}
 
+// Lookup table of one Huffman array: entry i (an L-bit window) holds the
+// symbol and length of the code that prefixes it.  The table is validated
+// (ascending symbols, lengths 1..L, some code of length L, Kraft sum <= 1),
+// the canonical codes are laid out in (length, symbol) order, and each of the
+// 2^L entries finds its code by binary search over the codes' left-justified
+// starts, so no thread fills a long run of entries.
 __global__ __launch_bounds__(kHT) void k_lut(const DecArr* arrs, uint32_t* lut_all, uint32_t* err) {
   __shared__ uint32_t wcnt[kHT / kWave * 16];
-  __shared__ uint32_t misc[64];
+  __shared__ uint32_t misc[80];
+  __shared__ uint32_t cstart[kAlphabet], centry[kAlphabet];
   const int a = blockIdx.x;
   const DecArr d = arrs[a];
   if (d.coder != 1) return;
@@ -759,13 +809,13 @@ __global__ __launch_bounds__(kHT) void k_lut(const DecArr* arrs, uint32_t* lut_a
     return;
   }
   const uint32_t* tab = reinterpret_cast<const uint32_t*>(d.data);
-  for (uint32_t i = t; i < (1u << L); i += kHT) lut[i] = 0;
-  if (t < 64) misc[t] = 0;
+  if (t < 80) misc[t] = 0;
   __syncthreads();
-  uint32_t* blc = misc;  // [16]
-  uint32_t* first = misc + 16;
-  uint32_t* run = misc + 32;
+  uint32_t* blc = misc;  // [16] codes per length
+  uint32_t* first = misc + 16;  // [16] first code per length
+  uint32_t* run = misc + 32;    // [16] codes of each length placed so far
   uint32_t* flags = misc + 48;  // [0] malformed entry, [1] has length L, [2] Kraft sum
+  uint32_t* cbase = misc + 64;  // [16] canonical index of each length's first code
   for (uint32_t j = t; j < U; j += kHT) {
     uint32_t e = tab[j];
     uint32_t sy = e & 0xFFFFu, l = (e >> 16) & 0xFFu;
@@ -784,10 +834,12 @@ __global__ __launch_bounds__(kHT) void k_lut(const DecArr* arrs, uint32_t* lut_a
     return;
   }
   if (t == 0) {
-    uint32_t code = 0;
+    uint32_t code = 0, base = 0;
     for (int l = 1; l <= kMaxLen; l++) {
       code = (code + blc[l - 1]) << 1;
       first[l] = code;
+      cbase[l] = base;
+      base += blc[l];
     }
   }
   __syncthreads();
@@ -806,11 +858,10 @@ __global__ __launch_bounds__(kHT) void k_lut(const DecArr* arrs, uint32_t* lut_a
     if (j < U) {
       uint32_t r = run[l] + rank;
       for (int w2 = 0; w2 < wave_id(); w2++) r += wcnt[w2 * 16 + l];
-      uint32_t code = first[l] + r;
+      const uint32_t code = first[l] + r;
       if (code < (1u << l)) {
-        uint32_t span = 1u << (L - l), start = code << (L - l);
-        uint32_t entry = (e & 0xFFFFu) | (l << 16);
-        for (uint32_t q = 0; q < span; q++) lut[start + q] = entry;
+        cstart[cbase[l] + r] = code << (L - l);
+        centry[cbase[l] + r] = (e & 0xFFFFu) | (l << 16);
       } else {
         atomicOr(err, kErrCorrupt);
       }
@@ -822,6 +873,19 @@ __global__ __launch_bounds__(kHT) void k_lut(const DecArr* arrs, uint32_t* lut_a
       run[t] += add;
     }
     __syncthreads();
+  }
+  // codes that overflowed their length were flagged above; the starts of the
+  // rest ascend in canonical order
+  for (uint32_t i = t; i < (1u << L); i += kHT) {
+    int lo = 0, hi = (int)U - 1;  // last code starting at or before i
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (cstart[mid] <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    const uint32_t e = centry[lo];
+    const uint32_t l = e >> 16;
+    lut[i] = (cstart[lo] <= i && i - cstart[lo] < (1u << (L - l))) ? e : 0u;
   }
 }
 
@@ -843,37 +907,51 @@ __device__ inline bool store_value(const DecArr& d, uint64_t i, uint64_t v) {
 // words per store.
 constexpr int kRound = 16;
 
-// MSB-first reader over one chunk's words.  Two words are always in flight
-// ahead of the 64-bit window, so the global load a lane needs next was issued
-// tens of symbols earlier instead of stalling the (divergent) refill.
+// MSB-first reader over one chunk's words, double-buffered in registers: the
+// words being consumed (cur, arrived) and the next block of kRdWords words
+// (nxt, in flight since the previous swap), so a load's latency is covered by
+// decoding a whole block (hundreds of bits) instead of one 32-bit refill.  The
+// word to append is picked by a select chain over cur (static register
+// indices, no scratch).
+constexpr int kRdWords = 8;
+
 struct BitReader {
   uint64_t buf;
   int nb;
-  uint64_t wp, wend;  // next word to load, end of the chunk
-  uint32_t n0, n1;    // prefetched words
-  int have;           // how many of n0, n1 are valid
+  int ci;              // next word of cur to append
+  uint64_t wp, wend;   // next word to load into nxt, end of the chunk
+  uint64_t rem;        // words not yet appended
+  uint32_t cur[kRdWords], nxt[kRdWords];
   const uint32_t* payload;
+  __device__ inline void load_block(uint32_t* dst) {
+#pragma unroll
+    for (int j = 0; j < kRdWords; j++) dst[j] = wp + j < wend ? payload[wp + j] : 0u;
+    wp += kRdWords;
+  }
   __device__ inline void start(const uint32_t* p, uint64_t beg, uint64_t end) {
     payload = p;
     wp = beg;
     wend = end;
+    rem = end - beg;
     buf = 0;
     nb = 0;
-    have = 0;
-    n0 = wp < wend ? payload[wp] : 0u;
-    if (wp < wend) { wp++; have = 1; }
-    n1 = wp < wend ? payload[wp] : 0u;
-    if (wp < wend) { wp++; have = 2; }
+    ci = 0;
+    load_block(cur);
+    load_block(nxt);
   }
   __device__ inline void refill() {
-    while (nb <= 32 && have > 0) {
-      buf |= (uint64_t)n0 << (32 - nb);
+    while (nb <= 32 && rem > 0) {
+      uint32_t w = cur[0];
+#pragma unroll
+      for (int j = 1; j < kRdWords; j++) w = ci == j ? cur[j] : w;
+      buf |= (uint64_t)w << (32 - nb);
       nb += 32;
-      n0 = n1;
-      have--;
-      if (wp < wend) {
-        n1 = payload[wp++];
-        have++;
+      rem--;
+      if (++ci == kRdWords) {
+#pragma unroll
+        for (int j = 0; j < kRdWords; j++) cur[j] = nxt[j];
+        load_block(nxt);
+        ci = 0;
       }
     }
   }
@@ -1043,55 +1121,64 @@ inline uint32_t gclamp(uint64_t g, uint32_t cap) {
 
 }  // namespace
 
-void launch_encode(const ArrSet& set, uint64_t max_n, int chunk_log2, ArrWork* work,
-                   uint32_t* chunk_words, uint64_t max_chunks, uint32_t* hist_part,
-                   unsigned long long* hist_max, uint8_t* huff_lens, uint32_t* huff_maxd,
-                   const RecHdr& h, const uint32_t* B_dev, uint8_t* out, uint64_t cap,
-                   unsigned long long* size_dev, uint32_t* err, bool hist_done, hipStream_t s) {
-  const int A = set.A;
-  {
-    const int nb = (int)gclamp((max_n + 8191) / 8192, kHistBlocks);
-    dim3 g(nb, A);
-    if (!hist_done)
-      LCP_TIMED("hist", max_n * 4ull * A, s, k_hist<<<g, kThreads, 0, s>>>(set, hist_part, hist_max));
-    k_hist_reduce<<<dim3((kAlphabet + kThreads - 1) / kThreads, A), kThreads, 0, s>>>(
-        set, hist_part, hist_max, work);
+uint32_t enc_hist_blocks(uint64_t n) { return gclamp((n + 8191) / 8192, kHistBlocks); }
+uint32_t enc_hist_copies(uint64_t n) {
+  const uint32_t c = (enc_hist_blocks(n) + 15) / 16;
+  return c > (uint32_t)kHistCopies ? (uint32_t)kHistCopies : c;
+}
+uint32_t enc_chunk_blocks(uint64_t n, int chunk_log2) {
+  return gclamp((n + (1ull << chunk_log2) - 1) >> chunk_log2, 1024);
+}
+uint32_t enc_fixed_blocks(uint64_t n) { return gclamp((n + 2047) / 2048, 1024); }
+
+void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, uint32_t* chunk_words,
+                   uint32_t* hist_part, unsigned long long* hist_max, uint8_t* huff_lens,
+                   uint32_t* huff_maxd, uint8_t* out, uint64_t cap, unsigned long long* offs,
+                   uint32_t* err, bool hist_done, hipStream_t s) {
+  const int NA = L.NA;
+  const uint32_t* pre_hist = L.pre;
+  const uint32_t* pre_chunk = L.pre + (NA + 1);
+  const uint32_t* pre_fixed = L.pre + 2 * (NA + 1);
+  if (!hist_done)
+    LCP_TIMED("hist", L.values * 4ull, s,
+              k_hist<<<L.hist_blocks, kThreads, 0, s>>>(L.arrs, pre_hist, NA, hist_part, hist_max));
+  k_hist_reduce<<<dim3((kAlphabet + kThreads - 1) / kThreads, NA), kThreads, 0, s>>>(
+      L.arrs, hist_part, hist_max, work);
+  // Few arrays: all halving counts side by side.  Many: the plain build first,
+  // then the halvings only for the arrays whose plain build is too deep.
+  if (NA <= 16) {
+    k_huff_lengths<<<dim3(NA, kHalvings), kHT, 0, s>>>(work, huff_lens, huff_maxd, 0, 0);
+  } else {
+    k_huff_lengths<<<dim3(NA, 1), kHT, 0, s>>>(work, huff_lens, huff_maxd, 0, 0);
+    k_huff_lengths<<<dim3(NA, kHalvings - 1), kHT, 0, s>>>(work, huff_lens, huff_maxd, 1, 1);
   }
-  k_huff_lengths<<<dim3(A, kHalvings), kHT, 0, s>>>(work, huff_lens, huff_maxd);
-  k_huff_codes<<<A, kHT, 0, s>>>(work, huff_lens, huff_maxd);
-  const uint64_t chunks = (max_n + (1ull << chunk_log2) - 1) >> chunk_log2;
-  {
-    dim3 g(gclamp(chunks, 1024), A);
-    LCP_TIMED("chunk_bits", max_n * 4ull * A, s, {
-      switch (chunk_log2) {
-        case 9: k_chunk_bits<2><<<g, kThreads, 0, s>>>(set, work, chunk_log2, chunk_words, max_chunks); break;
-        case 10: k_chunk_bits<4><<<g, kThreads, 0, s>>>(set, work, chunk_log2, chunk_words, max_chunks); break;
-        case 11: k_chunk_bits<8><<<g, kThreads, 0, s>>>(set, work, chunk_log2, chunk_words, max_chunks); break;
-        case 12: k_chunk_bits<16><<<g, kThreads, 0, s>>>(set, work, chunk_log2, chunk_words, max_chunks); break;
-        default: k_chunk_bits<1><<<g, kThreads, 0, s>>>(set, work, chunk_log2, chunk_words, max_chunks); break;
-      }
-    });
-  }
-  k_chunk_scan<<<A, kHT, 0, s>>>(work, chunk_log2, chunk_words, max_chunks);
-  k_layout<<<1, 64, 0, s>>>(work, h, B_dev, out, cap, size_dev, err);
-  {
-    const uint64_t max_words = (max_n * 64 + 31) / 32;
-    dim3 g(gclamp((max_words + kThreads - 1) / kThreads, 2048), A);
-    LCP_TIMED("pack_fixed", max_n * 6ull * A, s,
-              k_pack_fixed<<<g, kThreads, 0, s>>>(set, work, out, err));
-  }
+  k_huff_codes<<<NA, kHT, 0, s>>>(work, huff_lens, huff_maxd);
+  LCP_TIMED("chunk_bits", L.values * 4ull, s, {
+    switch (chunk_log2) {
+      case 9: k_chunk_bits<2><<<L.chunk_blocks, kThreads, 0, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, chunk_words); break;
+      case 10: k_chunk_bits<4><<<L.chunk_blocks, kThreads, 0, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, chunk_words); break;
+      case 11: k_chunk_bits<8><<<L.chunk_blocks, kThreads, 0, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, chunk_words); break;
+      case 12: k_chunk_bits<16><<<L.chunk_blocks, kThreads, 0, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, chunk_words); break;
+      default: k_chunk_bits<1><<<L.chunk_blocks, kThreads, 0, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, chunk_words); break;
+    }
+  });
+  k_chunk_scan<<<NA, kHT, 0, s>>>(L.arrs, work, chunk_log2, chunk_words);
+  k_layout<<<1, kHT, 0, s>>>(work, L.recs, L.R, out, cap, offs, err);
+  LCP_TIMED("pack_fixed", L.values * 6ull, s,
+            k_pack_fixed<<<L.fixed_blocks, kThreads, 0, s>>>(L.arrs, work, L.recs, pre_fixed, NA,
+                                                             out, err));
   {
     const uint32_t C = 1u << chunk_log2;
     const uint32_t max_words = (C * (kMaxLen + 63) + 31) / 32 + 1;
-    dim3 g(gclamp(chunks, 1024), A);
     const size_t shm = (size_t)max_words * 4;
-    LCP_TIMED("pack_huff", max_n * 6ull * A, s, {
+    const uint32_t g = L.chunk_blocks;
+    LCP_TIMED("pack_huff", L.values * 6ull, s, {
       switch (chunk_log2) {
-        case 9: k_pack_huff<2><<<g, kThreads, shm, s>>>(set, work, chunk_log2, chunk_words, max_chunks, max_words, out, err); break;
-        case 10: k_pack_huff<4><<<g, kThreads, shm, s>>>(set, work, chunk_log2, chunk_words, max_chunks, max_words, out, err); break;
-        case 11: k_pack_huff<8><<<g, kThreads, shm, s>>>(set, work, chunk_log2, chunk_words, max_chunks, max_words, out, err); break;
-        case 12: k_pack_huff<16><<<g, kThreads, shm, s>>>(set, work, chunk_log2, chunk_words, max_chunks, max_words, out, err); break;
-        default: k_pack_huff<1><<<g, kThreads, shm, s>>>(set, work, chunk_log2, chunk_words, max_chunks, max_words, out, err); break;
+        case 9: k_pack_huff<2><<<g, kThreads, shm, s>>>(L.arrs, work, L.recs, pre_chunk, NA, chunk_log2, chunk_words, max_words, out, err); break;
+        case 10: k_pack_huff<4><<<g, kThreads, shm, s>>>(L.arrs, work, L.recs, pre_chunk, NA, chunk_log2, chunk_words, max_words, out, err); break;
+        case 11: k_pack_huff<8><<<g, kThreads, shm, s>>>(L.arrs, work, L.recs, pre_chunk, NA, chunk_log2, chunk_words, max_words, out, err); break;
+        case 12: k_pack_huff<16><<<g, kThreads, shm, s>>>(L.arrs, work, L.recs, pre_chunk, NA, chunk_log2, chunk_words, max_words, out, err); break;
+        default: k_pack_huff<1><<<g, kThreads, shm, s>>>(L.arrs, work, L.recs, pre_chunk, NA, chunk_log2, chunk_words, max_words, out, err); break;
       }
     });
   }

@@ -5,6 +5,8 @@
 //   device-wide scans, run detection (non-empty blocks), symbol arrays with delta
 //   coding (Sec. 6.2.2), temporal residuals (Sec. 7.1), and the decode-side block
 //   expansion and FP32 reconstruction.
+#include <string.h>
+
 #include "lcp_internal.h"
 
 namespace lcp {
@@ -18,109 +20,6 @@ inline uint32_t grid_for(uint64_t n, uint64_t per_block, uint32_t cap = 1u << 20
   if (g < 1) g = 1;
   if (g > cap) g = cap;
   return (uint32_t)g;
-}
-
-// ------------------------------------------------------------------ extent
-// Two passes: every block reduces its share of one field to a (min, max) pair
-// of sortable keys, then one block per field reduces the partials (no contended
-// atomics on a single address).
-constexpr int kExtBlocks = 256;
-
-__global__ __launch_bounds__(kThreads) void k_extent(FieldPtrs x, uint64_t n, uint32_t* part,
-                                                     uint32_t* err) {
-  __shared__ uint32_t smn[kThreads / kWave], smx[kThreads / kWave];
-  const int f = blockIdx.y;
-  const float* p = x.p[f];
-  uint32_t mn = 0xFFFFFFFFu, mx = 0u, bad = 0u;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  // float4 body over the 16-byte aligned part, scalar head/tail
-  uint64_t head = (uint64_t)((16 - ((uintptr_t)p & 15)) & 15) / 4;
-  if (head > n) head = n;
-  uint64_t nv = (n - head) / 4;
-  const float4* p4 = reinterpret_cast<const float4*>(p + head);
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nv; i += stride) {
-    float4 v = p4[i];
-    float a[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-    for (int j = 0; j < 4; j++) {
-      uint32_t key = float_key(a[j]);
-      mn = min(mn, key);
-      mx = max(mx, key);
-      bad |= !__builtin_isfinite(a[j]);
-    }
-  }
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < head + (n - head) % 4;
-       i += stride) {
-    uint64_t idx = i < head ? i : head + 4 * nv + (i - head);
-    float v = p[idx];
-    uint32_t key = float_key(v);
-    mn = min(mn, key);
-    mx = max(mx, key);
-    bad |= !__builtin_isfinite(v);
-  }
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) {
-    mn = min(mn, (uint32_t)__shfl_xor((int)mn, d, kWave));
-    mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, kWave));
-    bad |= (uint32_t)__shfl_xor((int)bad, d, kWave);
-  }
-  if (lane_id() == 0) {
-    smn[wave_id()] = mn;
-    smx[wave_id()] = mx;
-    if (bad) atomicOr(err, kErrNonFinite);
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < kThreads / kWave; w++) {
-      mn = min(mn, smn[w]);
-      mx = max(mx, smx[w]);
-    }
-    part[2 * ((uint64_t)f * gridDim.x + blockIdx.x)] = mn;
-    part[2 * ((uint64_t)f * gridDim.x + blockIdx.x) + 1] = mx;
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void k_extent_final(const uint32_t* part, int nblocks,
-                                                           uint32_t* ext) {
-  const int f = blockIdx.x;
-  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
-  for (int b = threadIdx.x; b < nblocks; b += kThreads) {
-    mn = min(mn, part[2 * (f * nblocks + b)]);
-    mx = max(mx, part[2 * (f * nblocks + b) + 1]);
-  }
-#pragma unroll
-  for (int d = kWave / 2; d > 0; d >>= 1) {
-    mn = min(mn, (uint32_t)__shfl_xor((int)mn, d, kWave));
-    mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, kWave));
-  }
-  __shared__ uint32_t smn[kThreads / kWave], smx[kThreads / kWave];
-  if (lane_id() == 0) {
-    smn[wave_id()] = mn;
-    smx[wave_id()] = mx;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 1; w < kThreads / kWave; w++) {
-      mn = min(mn, smn[w]);
-      mx = max(mx, smx[w]);
-    }
-    ext[2 * f] = mn;
-    ext[2 * f + 1] = mx;
-  }
-}
-
-// ------------------------------------------------------------------ quantise + key
-__global__ __launch_bounds__(kThreads) void k_quant_key(FieldPtrs x, uint64_t n, GridDev g,
-                                                        int k, uint64_t bn0, uint64_t bn1,
-                                                        uint64_t* keys, uint32_t* vals) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    uint64_t b0 = (uint64_t)quantise(x.p[0][i], g.m[0], g.inv[0]) >> k;
-    uint64_t b1 = (uint64_t)quantise(x.p[1][i], g.m[1], g.inv[1]) >> k;
-    uint64_t b2 = (uint64_t)quantise(x.p[2][i], g.m[2], g.inv[2]) >> k;
-    keys[i] = b0 + bn0 * (b1 + bn1 * b2);  // Eq. 6, x fastest
-    vals[i] = (uint32_t)i;
-  }
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -263,83 +162,6 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(T* data, uint64_t n,
   }
 }
 
-// ------------------------------------------------------------------ runs
-// Non-empty blocks: a slot starts a block when its key differs from the previous
-// slot's.  flags_scan holds the inclusive count of block starts.
-__global__ __launch_bounds__(kThreads) void k_run_flags(const uint64_t* keys, uint64_t n,
-                                                        uint32_t* flags) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride)
-    flags[s] = (s == 0 || keys[s] != keys[s - 1]) ? 1u : 0u;
-}
-
-__global__ __launch_bounds__(kThreads) void k_runs_write(const uint64_t* keys,
-                                                         const uint32_t* scan, uint64_t n,
-                                                         uint64_t* ids, uint32_t* starts,
-                                                         uint32_t* B_dev) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
-    if (s == 0 || keys[s] != keys[s - 1]) {
-      uint32_t b = scan[s] - 1;
-      ids[b] = keys[s];
-      starts[b] = (uint32_t)s;
-    }
-    if (s == n - 1) *B_dev = scan[s];
-  }
-}
-
-// Delta coding of block ids and counts (Sec. 6.2.2): id deltas, zigzag of count
-// deltas.
-__global__ __launch_bounds__(kThreads) void k_block_syms(const uint64_t* ids,
-                                                         const uint32_t* starts,
-                                                         const uint32_t* B_dev, uint64_t n,
-                                                         uint64_t* v_id, uint64_t* v_cnt) {
-  const uint64_t B = *B_dev;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < B; b += stride) {
-    uint64_t id = ids[b];
-    v_id[b] = id - (b ? ids[b - 1] : 0);
-    int64_t c = (int64_t)((b + 1 < B ? (uint64_t)starts[b + 1] : n) - starts[b]);
-    int64_t cp = b ? (int64_t)(starts[b] - starts[b - 1]) : 0;
-    v_cnt[b] = zigzag64(c - cp);
-  }
-}
-
-// Slot-order symbols.  Each block of 256 threads covers 256 consecutive slots;
-// thread 0 also quantises the slot before the block so that every relative
-// position has its predecessor for the delta (mod p).
-__global__ __launch_bounds__(kThreads) void k_slot_syms(FieldPtrs x, int F, uint64_t n,
-                                                        GridDev g, int k, const uint32_t* perm,
-                                                        uint32_t* v_rel, uint32_t* v_sup,
-                                                        int32_t* q_slot) {
-  __shared__ uint32_t rel[3][kThreads + 1];
-  const uint64_t s0 = (uint64_t)blockIdx.x * kThreads;
-  const uint64_t s = s0 + threadIdx.x;
-  const uint32_t pm = (1u << k) - 1u;
-  const bool valid = s < n;
-  uint32_t i = valid ? perm[s] : 0;
-  if (valid) {
-    for (int f = 0; f < F; f++) {
-      int64_t q = quantise(x.p[f][i], g.m[f], g.inv[f]);
-      if (f < 3) rel[f][threadIdx.x + 1] = (uint32_t)q & pm;
-      else v_sup[(uint64_t)(f - 3) * n + s] = (uint32_t)q;
-      if (q_slot) q_slot[(uint64_t)f * n + s] = (int32_t)q;
-    }
-  }
-  if (threadIdx.x == 0) {
-    if (s0 == 0) {
-      rel[0][0] = rel[1][0] = rel[2][0] = 0;
-    } else {
-      uint32_t ip = perm[s0 - 1];
-      for (int d = 0; d < 3; d++) rel[d][0] = (uint32_t)quantise(x.p[d][ip], g.m[d], g.inv[d]) & pm;
-    }
-  }
-  __syncthreads();
-  if (valid)
-    for (int d = 0; d < 3; d++)
-      v_rel[(uint64_t)d * n + s] = (rel[d][threadIdx.x + 1] - rel[d][threadIdx.x]) & pm;
-}
-
 // LCP-T: the frame's codes on the reference grid, in the reference's slot order,
 // minus the reference codes (zigzag); the new codes become the next reference.
 // The frame must stay inside the grid's float32 margin (|x| + 2 eb < 2^E) and
@@ -446,6 +268,356 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
       if (m) atomicMax(&hist_max[(uint64_t)f * kHistCopies + copy], (unsigned long long)m);
     }
   }
+}
+
+// ------------------------------------------------------------------ spatial batch
+// Every frame of a batch gets whole workgroups; a workgroup finds its frame by
+// binary search in a prefix table of per-frame workgroup counts (R + 1 entries).
+__device__ inline int seg_of_block(const uint32_t* pre, int R, uint32_t b) {
+  int lo = 0, hi = R - 1;  // largest r with pre[r] <= b
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void k_extent_b(const SegDev* S, const uint32_t* pre, int R,
+                                                       uint32_t* part, uint32_t* err) {
+  __shared__ uint32_t smn[kThreads / kWave], smx[kThreads / kWave];
+  const int r = seg_of_block(pre, R, blockIdx.x);
+  const uint32_t lb = blockIdx.x - pre[r], nb = pre[r + 1] - pre[r];
+  const int f = blockIdx.y;
+  const float* p = S[r].x[f];
+  const uint64_t n = S[r].n;
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u, bad = 0u;
+  const uint64_t stride = (uint64_t)nb * blockDim.x;
+  const uint64_t t0 = (uint64_t)lb * blockDim.x + threadIdx.x;
+  // float4 body over the 16-byte aligned part, scalar head/tail
+  uint64_t head = (uint64_t)((16 - ((uintptr_t)p & 15)) & 15) / 4;
+  if (head > n) head = n;
+  const uint64_t nv = (n - head) / 4;
+  const float4* p4 = reinterpret_cast<const float4*>(p + head);
+  for (uint64_t i = t0; i < nv; i += stride) {
+    float4 v = p4[i];
+    float a[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+      uint32_t key = float_key(a[j]);
+      mn = min(mn, key);
+      mx = max(mx, key);
+      bad |= !__builtin_isfinite(a[j]);
+    }
+  }
+  for (uint64_t i = t0; i < head + (n - head) % 4; i += stride) {
+    uint64_t idx = i < head ? i : head + 4 * nv + (i - head);
+    float v = p[idx];
+    uint32_t key = float_key(v);
+    mn = min(mn, key);
+    mx = max(mx, key);
+    bad |= !__builtin_isfinite(v);
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    mn = min(mn, (uint32_t)__shfl_xor((int)mn, d, kWave));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, kWave));
+    bad |= (uint32_t)__shfl_xor((int)bad, d, kWave);
+  }
+  if (lane_id() == 0) {
+    smn[wave_id()] = mn;
+    smx[wave_id()] = mx;
+    if (bad) atomicOr(err, kErrNonFinite);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / kWave; w++) {
+      mn = min(mn, smn[w]);
+      mx = max(mx, smx[w]);
+    }
+    part[2 * ((uint64_t)f * gridDim.x + blockIdx.x)] = mn;
+    part[2 * ((uint64_t)f * gridDim.x + blockIdx.x) + 1] = mx;
+  }
+}
+
+// Workgroup (r, f): reduces frame r's partials of field f.
+__global__ __launch_bounds__(kThreads) void k_extent_final_b(const uint32_t* part, const uint32_t* pre,
+                                                             int R, int F, uint32_t total,
+                                                             uint32_t* ext) {
+  const int r = blockIdx.x, f = blockIdx.y;
+  uint32_t mn = 0xFFFFFFFFu, mx = 0u;
+  for (uint32_t b = pre[r] + threadIdx.x; b < pre[r + 1]; b += kThreads) {
+    mn = min(mn, part[2 * ((uint64_t)f * total + b)]);
+    mx = max(mx, part[2 * ((uint64_t)f * total + b) + 1]);
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    mn = min(mn, (uint32_t)__shfl_xor((int)mn, d, kWave));
+    mx = max(mx, (uint32_t)__shfl_xor((int)mx, d, kWave));
+  }
+  __shared__ uint32_t smn[kThreads / kWave], smx[kThreads / kWave];
+  if (lane_id() == 0) {
+    smn[wave_id()] = mn;
+    smx[wave_id()] = mx;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kThreads / kWave; w++) {
+      mn = min(mn, smn[w]);
+      mx = max(mx, smx[w]);
+    }
+    ext[(uint64_t)r * 2 * F + 2 * f] = mn;
+    ext[(uint64_t)r * 2 * F + 2 * f + 1] = mx;
+  }
+}
+
+// Eq. 5 and Eq. 6 per particle; the frame tag above the block id keeps frames
+// apart in the batch-wide sort.  vals = index within the frame.
+__global__ __launch_bounds__(kThreads) void k_quant_key_b(const SegDev* S, const uint32_t* pre,
+                                                          int R, uint64_t* keys, uint32_t* vals) {
+  const int r = seg_of_block(pre, R, blockIdx.x);
+  const SegDev& g = S[r];
+  const uint64_t n = g.n;
+  const uint64_t i0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg1k;
+  const int k = g.k;
+#pragma unroll
+  for (int j = 0; j < (int)(kSeg1k / kThreads); j++) {
+    const uint64_t i = i0 + (uint64_t)j * kThreads + threadIdx.x;
+    if (i < n) {
+      uint64_t b0 = (uint64_t)quantise(g.x[0][i], g.m[0], g.inv[0]) >> k;
+      uint64_t b1 = (uint64_t)quantise(g.x[1][i], g.m[1], g.inv[1]) >> k;
+      uint64_t b2 = (uint64_t)quantise(g.x[2][i], g.m[2], g.inv[2]) >> k;
+      keys[g.off + i] = g.key_hi | (b0 + g.bn0 * (b1 + g.bn1 * b2));  // Eq. 6, x fastest
+      vals[g.off + i] = (uint32_t)i;
+    }
+  }
+}
+
+// A slot starts a non-empty block when it is its frame's first slot or its key
+// differs from the previous slot's.
+__global__ __launch_bounds__(kThreads) void k_run_flags_b(const uint64_t* keys, const SegDev* S,
+                                                          const uint32_t* pre, int R,
+                                                          uint32_t* flags) {
+  const int r = seg_of_block(pre, R, blockIdx.x);
+  const uint64_t n = S[r].n, off = S[r].off;
+  const uint64_t i0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg1k;
+#pragma unroll
+  for (int j = 0; j < (int)(kSeg1k / kThreads); j++) {
+    const uint64_t i = i0 + (uint64_t)j * kThreads + threadIdx.x;
+    if (i < n) flags[off + i] = (i == 0 || keys[off + i] != keys[off + i - 1]) ? 1u : 0u;
+  }
+}
+
+__global__ __launch_bounds__(kThreads) void k_runs_write_b(const uint64_t* keys,
+                                                           const uint32_t* scan, const SegDev* S,
+                                                           const uint32_t* pre, int R,
+                                                           uint64_t* ids, uint32_t* starts,
+                                                           uint32_t* rstart, uint32_t* Bs) {
+  const int r = seg_of_block(pre, R, blockIdx.x);
+  const uint64_t n = S[r].n, off = S[r].off, mask = S[r].id_mask;
+  const uint64_t i0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg1k;
+#pragma unroll
+  for (int j = 0; j < (int)(kSeg1k / kThreads); j++) {
+    const uint64_t i = i0 + (uint64_t)j * kThreads + threadIdx.x;
+    if (i >= n) continue;
+    const uint64_t g = off + i;
+    if (i == 0 || keys[g] != keys[g - 1]) {
+      const uint32_t b = scan[g] - 1;
+      ids[b] = keys[g] & mask;
+      starts[b] = (uint32_t)g;
+      if (i == 0) rstart[r] = b;
+    }
+    if (i == n - 1) {
+      Bs[r] = scan[g] - (off ? scan[off - 1] : 0u);
+      if (r == R - 1) rstart[R] = scan[g];
+    }
+  }
+}
+
+// Delta coding of block ids and counts (Sec. 6.2.2) per frame: id deltas,
+// zigzag of count deltas; both restart at each frame's first block.
+__global__ __launch_bounds__(kThreads) void k_block_syms_b(const uint64_t* ids,
+                                                           const uint32_t* starts,
+                                                           const uint32_t* rstart, int R,
+                                                           const SegDev* S, uint64_t ntot,
+                                                           uint64_t* v_id, uint64_t* v_cnt) {
+  __shared__ uint32_t rs[kMaxBatch + 1];
+  for (int j = threadIdx.x; j <= R; j += kThreads) rs[j] = rstart[j];
+  __syncthreads();
+  const uint64_t B = rs[R];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < B; b += stride) {
+    int lo = 0, hi = R - 1;  // frame of block b: largest r with rs[r] <= b
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (rs[mid] <= b) lo = mid;
+      else hi = mid - 1;
+    }
+    const bool first = b == rs[lo];
+    const uint64_t dst = S[lo].off + (b - rs[lo]);
+    v_id[dst] = ids[b] - (first ? 0 : ids[b - 1]);
+    const int64_t c = (int64_t)((b + 1 < B ? (uint64_t)starts[b + 1] : ntot) - starts[b]);
+    const int64_t cp = first ? 0 : (int64_t)(starts[b] - starts[b - 1]);
+    v_cnt[dst] = zigzag64(c - cp);
+  }
+}
+
+// Slot-order symbols, 256 slots per workgroup; thread 0 also quantises the slot
+// before the workgroup's first so that every relative position has its
+// predecessor for the delta (mod p), which restarts at each frame's first slot.
+__global__ __launch_bounds__(kThreads) void k_slot_syms_b(const SegDev* S, const uint32_t* pre,
+                                                          int R, int F, const uint32_t* perm,
+                                                          uint64_t ntot, uint32_t* v_rel,
+                                                          uint32_t* v_sup, int32_t* q_slot) {
+  __shared__ uint32_t rel[3][kThreads + 1];
+  const int r = seg_of_block(pre, R, blockIdx.x);
+  const SegDev& g = S[r];
+  const uint64_t n = g.n, off = g.off;
+  const uint64_t s0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg256;
+  const uint64_t s = s0 + threadIdx.x;
+  const uint32_t pm = (1u << g.k) - 1u;
+  const bool valid = s < n;
+  const uint32_t i = valid ? perm[off + s] : 0;
+  if (valid) {
+    for (int f = 0; f < F; f++) {
+      int64_t q = quantise(g.x[f][i], g.m[f], g.inv[f]);
+      if (f < 3) rel[f][threadIdx.x + 1] = (uint32_t)q & pm;
+      else v_sup[(uint64_t)(f - 3) * ntot + off + s] = (uint32_t)q;
+      if (q_slot) q_slot[(uint64_t)f * ntot + off + s] = (int32_t)q;
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (s0 == 0) {
+      rel[0][0] = rel[1][0] = rel[2][0] = 0;
+    } else {
+      const uint32_t ip = perm[off + s0 - 1];
+      for (int d = 0; d < 3; d++) rel[d][0] = (uint32_t)quantise(g.x[d][ip], g.m[d], g.inv[d]) & pm;
+    }
+  }
+  __syncthreads();
+  if (valid)
+    for (int d = 0; d < 3; d++)
+      v_rel[(uint64_t)d * ntot + off + s] = (rel[d][threadIdx.x + 1] - rel[d][threadIdx.x]) & pm;
+}
+
+__global__ __launch_bounds__(kThreads) void k_copy_perm_b(const uint32_t* perm, const SegDev* S,
+                                                          const uint32_t* pre, int R,
+                                                          uint32_t* const* dst) {
+  const int r = seg_of_block(pre, R, blockIdx.x);
+  uint32_t* d = dst[r];
+  if (!d) return;
+  const uint64_t n = S[r].n, off = S[r].off;
+  const uint64_t i0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg1k;
+#pragma unroll
+  for (int j = 0; j < (int)(kSeg1k / kThreads); j++) {
+    const uint64_t i = i0 + (uint64_t)j * kThreads + threadIdx.x;
+    if (i < n) d[i] = perm[off + i];
+  }
+}
+
+// ------------------------------------------------------------------ spatial batch decode
+// Frames of a decode batch are concatenated like an encode batch: frame r owns
+// slots [off, off + n) and blocks [boff, boff + B).  Per-frame inclusive scans
+// are a batch-wide scan minus the scan value just before the frame.
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_seg_bases(const T* X, uint64_t stride,
+                                                        const DSegDev* D, int R, int by_block,
+                                                        T* bases) {
+  const int r = blockIdx.x * kThreads + threadIdx.x;
+  const int d = blockIdx.y;
+  if (r >= R) return;
+  const uint64_t start = by_block ? D[r].boff : D[r].off;
+  bases[(uint64_t)d * R + r] = start ? X[(uint64_t)d * stride + start - 1] : (T)0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_seg_rebase(T* X, uint64_t stride, const DSegDev* D,
+                                                         const uint32_t* pre, int R, int by_block,
+                                                         const T* bases) {
+  const int r = seg_of_block(pre, R, blockIdx.x);
+  const int d = blockIdx.y;
+  const uint64_t start = by_block ? D[r].boff : D[r].off;
+  const uint64_t len = by_block ? D[r].B : D[r].n;
+  const T base = bases[(uint64_t)d * R + r];
+  const uint64_t i0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg1k;
+#pragma unroll
+  for (int j = 0; j < (int)(kSeg1k / kThreads); j++) {
+    const uint64_t i = i0 + (uint64_t)j * kThreads + threadIdx.x;
+    if (i < len) X[(uint64_t)d * stride + start + i] -= base;
+  }
+}
+
+// Per block: validate id / count, corner of the block in quantisation bins, and
+// a start mark for the slot -> block expansion (every block but the batch's
+// first).  ids and cnt hold per-frame inclusive scans of the decoded deltas;
+// cum the batch-wide inclusive scan of the counts (slot ends).
+__global__ __launch_bounds__(kThreads) void k_s_blocks_b(const uint64_t* ids, const uint64_t* cnt,
+                                                         const uint64_t* cum, const DSegDev* D,
+                                                         const uint32_t* pre, int R, uint64_t Btot,
+                                                         uint64_t ntot, uint32_t* corner,
+                                                         uint32_t* mark, uint32_t* err) {
+  const int r = seg_of_block(pre, R, blockIdx.x);
+  const DSegDev& g = D[r];
+  const uint64_t j0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg1k;
+#pragma unroll
+  for (int u = 0; u < (int)(kSeg1k / kThreads); u++) {
+    const uint64_t jb = j0 + (uint64_t)u * kThreads + threadIdx.x;
+    if (jb >= g.B) continue;
+    const uint64_t j = g.boff + jb;
+    const uint64_t id = ids[j];
+    const uint64_t c = cnt[j];
+    bool bad = id >= g.total_blocks || (jb > 0 && id <= ids[j - 1]) || c < 1 || c > g.n ||
+               cum[j] > g.off + g.n;
+    if (jb == g.B - 1 && cum[j] != g.off + g.n) bad = true;
+    if (bad) {
+      atomicOr(err, kErrCorrupt);
+      continue;
+    }
+    const uint64_t start = cum[j] - c;
+    const uint64_t bx = id % g.bn0, rest = id / g.bn0;
+    const uint64_t by = rest % g.bn1, bz = rest / g.bn1;
+    corner[j] = (uint32_t)(bx << g.k);
+    corner[Btot + j] = (uint32_t)(by << g.k);
+    corner[2 * Btot + j] = (uint32_t)(bz << g.k);
+    if (j > 0 && start < ntot) mark[start] = 1u;
+  }
+}
+
+// q = corner + relative position (fields 0-2) or the raw code (supplementary
+// fields), then the float32 reconstruction into the frame's output arrays.
+// blk holds the batch-wide block index of every slot, v the decoded slot
+// symbols ([F][ntot]; relative positions already scanned per frame).
+__global__ __launch_bounds__(kThreads) void k_s_recon_b(const uint32_t* blk, const uint32_t* corner,
+                                                        const uint32_t* v, const DSegDev* D,
+                                                        const uint32_t* pre, int R, int F,
+                                                        uint64_t Btot, uint64_t ntot,
+                                                        uint32_t* err) {
+  const int r = seg_of_block(pre, R, blockIdx.x);
+  const DSegDev& g = D[r];
+  const uint32_t pm = (1u << g.k) - 1u;
+  const uint64_t s0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg1k;
+  bool bad = false;
+#pragma unroll
+  for (int u = 0; u < (int)(kSeg1k / kThreads); u++) {
+    const uint64_t s = s0 + (uint64_t)u * kThreads + threadIdx.x;
+    if (s >= g.n) continue;
+    const uint64_t gs = g.off + s;
+    const uint64_t b = blk[gs];
+    if (b < g.boff || b >= g.boff + g.B) {
+      bad = true;
+      continue;
+    }
+    for (int f = 0; f < F; f++) {
+      uint64_t q = f < 3 ? (uint64_t)corner[(uint64_t)f * Btot + b] + (v[(uint64_t)f * ntot + gs] & pm)
+                         : (uint64_t)v[(uint64_t)f * ntot + gs];
+      if (q >= (uint64_t)kQLimit) {
+        bad = true;
+        q = 0;
+      }
+      g.out[f][s] = reconstruct((int64_t)q, g.eb_q[f], g.m[f]);
+    }
+  }
+  if (bad) atomicOr(err, kErrCorrupt);
 }
 
 // ------------------------------------------------------------------ decode side
@@ -562,6 +734,14 @@ __global__ void k_gather_headers(const uint64_t* tab, int stage, uint8_t* dst) {
   for (uint64_t w = threadIdx.x; w < words; w += blockDim.x) d[w] = src[w];
 }
 
+// Small host tables travel as a kernel argument: no copy-engine round trip.
+struct InstallArg {
+  uint32_t w[kInstallWords];
+};
+__global__ void k_install(InstallArg a, uint32_t* dst, uint32_t words) {
+  for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = a.w[i];
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -576,19 +756,48 @@ __global__ void k_copy_u32(const uint32_t* src, uint32_t* dst, uint64_t n) {
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
-void launch_extent(const FieldPtrs& x, int F, uint64_t n, uint32_t* ext, uint32_t* part,
-                   uint32_t* err, hipStream_t s) {
-  uint32_t nb = grid_for(n / 4 + 1, kThreads * 4, kExtBlocks);
-  LCP_TIMED("extent", (uint64_t)F * n * 4, s,
-            k_extent<<<dim3(nb, F), kThreads, 0, s>>>(x, n, part, err));
-  k_extent_final<<<F, kThreads, 0, s>>>(part, (int)nb, ext);
+uint32_t seg_ext_blocks(uint64_t n) { return grid_for(n / 4 + 1, kThreads * 4, kSegExtCap); }
+
+void launch_extent_b(const SegDev* S, const uint32_t* pre_ext, uint32_t ext_blocks, int R, int F,
+                     uint32_t* ext, uint32_t* part, uint32_t* err, uint64_t bytes, hipStream_t s) {
+  LCP_TIMED("extent", bytes, s,
+            k_extent_b<<<dim3(ext_blocks, F), kThreads, 0, s>>>(S, pre_ext, R, part, err));
+  k_extent_final_b<<<dim3(R, F), kThreads, 0, s>>>(part, pre_ext, R, F, ext_blocks, ext);
 }
 
-void launch_quant_key(const FieldPtrs& x, uint64_t n, const GridDev& g, int k, uint64_t bn0,
-                      uint64_t bn1, uint64_t* keys, uint32_t* vals, hipStream_t s) {
-  LCP_TIMED("quant_key", n * (12 + 12), s,
-            k_quant_key<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(
-                x, n, g, k, bn0, bn1, keys, vals));
+void launch_quant_key_b(const SegDev* S, const uint32_t* pre_1k, uint32_t blocks, int R,
+                        uint64_t* keys, uint32_t* vals, uint64_t ntot, hipStream_t s) {
+  LCP_TIMED("quant_key", ntot * (12 + 12), s,
+            k_quant_key_b<<<blocks, kThreads, 0, s>>>(S, pre_1k, R, keys, vals));
+}
+
+void launch_runs_b(const uint64_t* keys, const SegDev* S, const uint32_t* pre_1k, uint32_t blocks,
+                   int R, uint64_t ntot, uint32_t* flags_scan, uint64_t* ids, uint32_t* starts,
+                   uint32_t* rstart, uint32_t* Bs, uint32_t* tmp32, hipStream_t s) {
+  k_run_flags_b<<<blocks, kThreads, 0, s>>>(keys, S, pre_1k, R, flags_scan);
+  scan_device<uint32_t>(flags_scan, ntot, nullptr, false, tmp32, s);
+  k_runs_write_b<<<blocks, kThreads, 0, s>>>(keys, flags_scan, S, pre_1k, R, ids, starts, rstart, Bs);
+}
+
+void launch_block_syms_b(const uint64_t* ids, const uint32_t* starts, const uint32_t* rstart,
+                         int R, const SegDev* S, uint64_t ntot, uint64_t* v_id, uint64_t* v_cnt,
+                         hipStream_t s) {
+  k_block_syms_b<<<grid_for(ntot, kThreads * 4, 1u << 16), kThreads, 0, s>>>(
+      ids, starts, rstart, R, S, ntot, v_id, v_cnt);
+}
+
+void launch_slot_syms_b(const SegDev* S, const uint32_t* pre_256, uint32_t blocks, int R, int F,
+                        const uint32_t* perm, uint64_t ntot, uint32_t* v_rel, uint32_t* v_sup,
+                        int32_t* q_slot, hipStream_t s) {
+  uint64_t bytes = ntot * (4 + 4ull * F + 4ull * F + (q_slot ? 4ull * F : 0));
+  LCP_TIMED("slot_syms", bytes, s,
+            k_slot_syms_b<<<blocks, kThreads, 0, s>>>(S, pre_256, R, F, perm, ntot, v_rel, v_sup,
+                                                     q_slot));
+}
+
+void launch_copy_perm_b(const uint32_t* perm, const SegDev* S, const uint32_t* pre_1k,
+                        uint32_t blocks, int R, uint32_t* const* dst, hipStream_t s) {
+  k_copy_perm_b<<<blocks, kThreads, 0, s>>>(perm, S, pre_1k, R, dst);
 }
 
 int radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint64_t n, int bits,
@@ -638,27 +847,32 @@ template void scan_device<uint32_t>(uint32_t*, uint64_t, const uint32_t*, bool, 
 template void scan_device<uint64_t>(uint64_t*, uint64_t, const uint32_t*, bool, uint64_t*,
                                     hipStream_t);
 
-void launch_runs(const uint64_t* keys, uint64_t n, uint32_t* flags_scan, uint64_t* ids,
-                 uint32_t* starts, uint32_t* B_dev, uint32_t* tmp32, hipStream_t s) {
-  uint32_t g = grid_for(n, kThreads * 4, 1u << 16);
-  k_run_flags<<<g, kThreads, 0, s>>>(keys, n, flags_scan);
-  scan_device<uint32_t>(flags_scan, n, nullptr, false, tmp32, s);
-  k_runs_write<<<g, kThreads, 0, s>>>(keys, flags_scan, n, ids, starts, B_dev);
+template <typename T>
+void seg_rebase(T* X, uint64_t stride, int nd, const DSegDev* D, const uint32_t* pre,
+                uint32_t blocks, int R, bool by_block, T* bases, hipStream_t s) {
+  k_seg_bases<T><<<dim3((R + kThreads - 1) / kThreads, nd), kThreads, 0, s>>>(X, stride, D, R,
+                                                                            by_block, bases);
+  k_seg_rebase<T><<<dim3(blocks, nd), kThreads, 0, s>>>(X, stride, D, pre, R, by_block, bases);
+}
+template void seg_rebase<uint32_t>(uint32_t*, uint64_t, int, const DSegDev*, const uint32_t*,
+                                   uint32_t, int, bool, uint32_t*, hipStream_t);
+template void seg_rebase<uint64_t>(uint64_t*, uint64_t, int, const DSegDev*, const uint32_t*,
+                                   uint32_t, int, bool, uint64_t*, hipStream_t);
+
+void launch_s_blocks_b(const uint64_t* ids, const uint64_t* cnt, const uint64_t* cum,
+                       const DSegDev* D, const uint32_t* pre_blk, uint32_t blocks, int R,
+                       uint64_t Btot, uint64_t ntot, uint32_t* corner, uint32_t* mark,
+                       uint32_t* err, hipStream_t s) {
+  k_s_blocks_b<<<blocks, kThreads, 0, s>>>(ids, cnt, cum, D, pre_blk, R, Btot, ntot, corner, mark,
+                                           err);
 }
 
-void launch_block_syms(const uint64_t* ids, const uint32_t* starts, const uint32_t* B_dev,
-                       uint64_t n, uint64_t* v_id, uint64_t* v_cnt, hipStream_t s) {
-  k_block_syms<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(ids, starts, B_dev, n,
-                                                                        v_id, v_cnt);
-}
-
-void launch_slot_syms(const FieldPtrs& x, int F, uint64_t n, const GridDev& g, int k,
-                      const uint32_t* perm, uint32_t* v_rel, uint32_t* v_sup, int32_t* q_slot,
-                      hipStream_t s) {
-  uint64_t bytes = n * (4 + 4ull * F + 4ull * F + (q_slot ? 4ull * F : 0));
-  LCP_TIMED("slot_syms", bytes, s,
-            k_slot_syms<<<(uint32_t)((n + kThreads - 1) / kThreads), kThreads, 0, s>>>(
-                x, F, n, g, k, perm, v_rel, v_sup, q_slot));
+void launch_s_recon_b(const uint32_t* blk, const uint32_t* corner, const uint32_t* v,
+                      const DSegDev* D, const uint32_t* pre_slot, uint32_t blocks, int R, int F,
+                      uint64_t Btot, uint64_t ntot, uint32_t* err, hipStream_t s) {
+  LCP_TIMED("s_recon", ntot * (4 + 12 + 8ull * F), s,
+            k_s_recon_b<<<blocks, kThreads, 0, s>>>(blk, corner, v, D, pre_slot, R, F, Btot, ntot,
+                                                    err));
 }
 
 inline bool al16(const void* p) { return ((uintptr_t)p & 15) == 0; }
@@ -699,6 +913,20 @@ void launch_t_recon(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,
 
 void launch_gather_headers(const uint64_t* tab, int nrec, int stage, uint8_t* dst, hipStream_t s) {
   if (nrec) k_gather_headers<<<nrec, 128, 0, s>>>(tab, stage, dst);
+}
+
+void launch_install(const void* src, void* dst, size_t bytes, hipStream_t s) {
+  const uint8_t* sp = static_cast<const uint8_t*>(src);
+  uint8_t* dp = static_cast<uint8_t*>(dst);
+  while (bytes) {
+    const size_t chunk = bytes < (size_t)kInstallWords * 4 ? bytes : (size_t)kInstallWords * 4;
+    InstallArg a;
+    memcpy(a.w, sp, chunk);
+    k_install<<<1, 256, 0, s>>>(a, reinterpret_cast<uint32_t*>(dp), (uint32_t)(chunk / 4));
+    sp += chunk;
+    dp += chunk;
+    bytes -= chunk;
+  }
 }
 
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {

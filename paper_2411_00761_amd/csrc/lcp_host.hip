@@ -71,28 +71,46 @@ struct lcp_plan_s {
   int k = 0;
   int F = 3;
   int chunk_log2 = 10;
-  uint64_t N = 0;           // max particles
-  uint64_t max_chunks = 0;  // per array
+  uint64_t N = 0;   // max particles per frame
+  uint64_t NB = 0;  // max particles per spatial batch (>= N)
+  int RB = 1;       // max frames per spatial batch
+  int NAmax = 0;    // max coded arrays per encode launch set
+  uint64_t hist_copies = 0, cw_cap = 0;
   std::vector<void*> allocs;
   size_t allocated = 0;
 
-  // scratch
+  // scratch (batch-wide arrays hold NB slots)
   uint64_t *keys0, *keys1, *ids, *v_id, *v_cnt;
   uint32_t *vals0, *vals1, *hist, *flags, *starts, *v_slot, *chunk_words, *lut, *corner;
   uint64_t* scan_tmp;
   size_t scan_tmp_n;
   ArrWork* work;
-  uint32_t* small;  // [0] B, [1] err, [2..2+2F) extent keys
-  unsigned long long* size_dev;
+  // device return block (one read back per sync): [0] error word, [1, RB + 2)
+  // record offsets, then RB x 2F extent keys; ret_host is its pinned mirror
+  unsigned long long *ret_dev, *ret_host;
+  uint32_t* err;  // the error word (low half of ret_dev[0])
   uint8_t* rec_tmp;  // second record (temporal candidate)
   uint64_t rec_tmp_cap;
-  uint32_t* host_small;  // pinned mirror of `small`
-  unsigned long long* host_size;
   uint32_t* ext_part;    // extent partials
-  uint32_t* hist_part;   // per-workgroup histograms
+  uint32_t* hist_part;   // spread histogram copies
   unsigned long long* hist_max;
   uint8_t* huff_lens;    // candidate code lengths per (array, halving count)
   uint32_t* huff_maxd;
+  // spatial batch tables (pinned host staging + device mirrors)
+  SegDev *seg_host, *seg_dev;
+  uint32_t *segpre_host, *segpre_dev;  // [3][RB + 1]
+  uint32_t* ext_dev;                   // [RB][2F] extent keys (in ret_dev)
+  uint32_t *rstart, *Bs;               // [RB + 1], [RB]
+  uint32_t **permdst_host, **permdst_dev;
+  // spatial decode batch tables
+  DSegDev *dseg_host, *dseg_dev;
+  uint32_t *dpre_host, *dpre_dev;  // [2][kMaxBatchFrames + 1]: slot and block workgroups
+  unsigned long long* segbase;     // [3][kMaxBatchFrames] scan bases
+  // encoder tables
+  EncArr *earr_host, *earr_dev;
+  EncRec *erec_host, *erec_dev;
+  uint32_t *epre_host, *epre_dev;  // [3][NAmax + 1]
+  unsigned long long* offs_dev;  // [RB + 1] record offsets (in ret_dev)
   // batched decode staging (pinned host + device mirrors)
   uint8_t *hdr_host, *hdr_dev;
   uint64_t *blobtab_host, *blobtab_dev;
@@ -151,6 +169,27 @@ lcp_status dalloc(lcp_plan_s* P, T** out, size_t elems) {
   return LCP_OK;
 }
 
+// Host table -> device: small tables through kernel arguments (a copy-engine
+// transfer costs tens of microseconds on the stream), large ones by copy from
+// pinned memory (the source must then stay untouched until the stream syncs).
+lcp_status upload(const void* host, void* dev, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return LCP_OK;
+  if (bytes % 4 == 0 && bytes <= 4 * (size_t)kInstallWords * 4) {
+    launch_install(host, dev, bytes, s);
+    return LCP_OK;
+  }
+  return hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, s) == hipSuccess ? LCP_OK
+                                                                               : LCP_ERR_DEVICE;
+}
+
+// Reads back the first `words` u64 of the return block and waits for the stream.
+lcp_status read_ret(lcp_plan_s* P, size_t words, hipStream_t s) {
+  HIP_OK(hipMemcpyAsync(P->ret_host, P->ret_dev, words * 8, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  return LCP_OK;
+}
+uint32_t host_err(const lcp_plan_s* P) { return (uint32_t)(P->ret_host[0] & 0xFFFFFFFFull); }
+
 void timer_collect(lcp_plan_s* P) {
   for (size_t i = 0; i < P->ev_pending.size(); i++) {
     float ms = 0;
@@ -196,24 +235,62 @@ GridDev to_dev(const HostGrid* g, int F) {
   return d;
 }
 
-// ------------------------------------------------------------------ extent
-lcp_status extent(lcp_plan_s* P, const float* const* x, uint64_t n, float* lo, float* hi,
-                  hipStream_t s) {
-  FieldPtrs fp;
-  memset(&fp, 0, sizeof(fp));
-  for (int f = 0; f < P->F; f++) fp.p[f] = x[f];
-  launch_fill_u32(P->small + 1, 1, 0u, s);
-  launch_extent(fp, P->F, n, P->small + 2, P->ext_part, P->small + 1, s);
-  HIP_OK(hipMemcpyAsync(P->host_small, P->small, sizeof(uint32_t) * (2 + 2 * P->F),
-                        hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  if (P->host_small[1] & kErrNonFinite) return LCP_ERR_ARG;
-  for (int f = 0; f < P->F; f++) {
-    float a = key_float(P->host_small[2 + 2 * f]);
-    float b = key_float(P->host_small[3 + 2 * f]);
-    lo[f] = a == 0.0f ? 0.0f : a;  // one zero: +0
-    hi[f] = b == 0.0f ? 0.0f : b;
+// ------------------------------------------------------------------ spatial batch tables
+// The caller fills seg_host[r].x and .n; frames are placed back to back.
+struct SegLayout {
+  uint32_t ext_blocks = 0, blocks_1k = 0, blocks_256 = 0;
+  uint64_t ntot = 0;
+};
+
+lcp_status upload_segs(lcp_plan_s* P, int R, SegLayout* L, hipStream_t s) {
+  uint32_t* pe = P->segpre_host;
+  uint32_t* p1 = pe + (R + 1);
+  uint32_t* p2 = p1 + (R + 1);
+  SegLayout l;
+  for (int r = 0; r < R; r++) {
+    SegDev& g = P->seg_host[r];
+    g.off = l.ntot;
+    l.ntot += g.n;
+    pe[r] = l.ext_blocks;
+    p1[r] = l.blocks_1k;
+    p2[r] = l.blocks_256;
+    l.ext_blocks += seg_ext_blocks(g.n);
+    l.blocks_1k += (uint32_t)((g.n + kSeg1k - 1) / kSeg1k);
+    l.blocks_256 += (uint32_t)((g.n + kSeg256 - 1) / kSeg256);
   }
+  pe[R] = l.ext_blocks;
+  p1[R] = l.blocks_1k;
+  p2[R] = l.blocks_256;
+  if (l.ntot > P->NB) return LCP_ERR_ARG;
+  lcp_status st = upload(P->seg_host, P->seg_dev, sizeof(SegDev) * R, s);
+  if (!st) st = upload(P->segpre_host, P->segpre_dev, sizeof(uint32_t) * 3 * (R + 1), s);
+  if (st) return st;
+  *L = l;
+  return LCP_OK;
+}
+
+// ------------------------------------------------------------------ extent
+// Per-field minima and maxima of R frames (seg_host[r].x / .n), one sync.
+lcp_status extent_batch(lcp_plan_s* P, int R, float (*lo)[kMaxF], float (*hi)[kMaxF],
+                        hipStream_t s) {
+  const int F = P->F;
+  SegLayout L;
+  lcp_status st = upload_segs(P, R, &L, s);
+  if (st) return st;
+  launch_fill_u32(P->err, 1, 0u, s);
+  launch_extent_b(P->seg_dev, P->segpre_dev, L.ext_blocks, R, F, P->ext_dev, P->ext_part,
+                  P->err, (uint64_t)F * L.ntot * 4, s);
+  const size_t ext_word0 = (size_t)(reinterpret_cast<unsigned long long*>(P->ext_dev) - P->ret_dev);
+  if ((st = read_ret(P, ext_word0 + ((size_t)R * 2 * F + 1) / 2, s))) return st;
+  if (host_err(P) & kErrNonFinite) return LCP_ERR_ARG;
+  const uint32_t* ext = reinterpret_cast<const uint32_t*>(P->ret_host + ext_word0);
+  for (int r = 0; r < R; r++)
+    for (int f = 0; f < F; f++) {
+      float a = key_float(ext[(size_t)r * 2 * F + 2 * f]);
+      float b = key_float(ext[(size_t)r * 2 * F + 2 * f + 1]);
+      lo[r][f] = a == 0.0f ? 0.0f : a;  // one zero: +0
+      hi[r][f] = b == 0.0f ? 0.0f : b;
+    }
   return LCP_OK;
 }
 
@@ -239,89 +316,264 @@ lcp_status field_eb(const lcp_params& p, int F, const float* lo, const float* hi
   return LCP_OK;
 }
 
-// ------------------------------------------------------------------ encode driver
-lcp_status finish_record(lcp_plan_s* P, uint64_t* size, uint32_t* flags, hipStream_t s) {
-  HIP_OK(hipMemcpyAsync(P->host_size, P->size_dev, sizeof(unsigned long long),
-                        hipMemcpyDeviceToHost, s));
-  HIP_OK(hipMemcpyAsync(P->host_small + 1, P->small + 1, sizeof(uint32_t),
-                        hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
-  if (g_timer_plan == P) timer_collect(P);
-  *size = *P->host_size;
-  if (flags) *flags = P->host_small[1];
-  if (P->host_small[1] & kErrCapacity) return LCP_ERR_CAPACITY;
+// ------------------------------------------------------------------ encoder tables
+struct EncBuild {
+  int NA = 0, R = 0;
+  uint32_t copies = 0;
+  uint64_t cw = 0, values = 0;
+  std::vector<uint32_t> hb, cb, fb;
+};
+
+// Adds one array of at most nb values to record rec; copy0 < 0 places its
+// spread histogram copies after the previous array's.
+lcp_status enc_add(lcp_plan_s* P, EncBuild& B, const ArrIn& in, uint64_t nb, int rec, int copy0,
+                   uint32_t copies) {
+  if (B.NA >= P->NAmax) return LCP_ERR_ARG;
+  EncArr& e = P->earr_host[B.NA];
+  memset(&e, 0, sizeof(e));
+  e.in = in;
+  e.rec = (uint32_t)rec;
+  if (copy0 < 0) {
+    e.copy0 = B.copies;
+    e.copies = enc_hist_copies(nb);
+    B.copies += e.copies;
+  } else {
+    e.copy0 = (uint32_t)copy0;
+    e.copies = copies;
+    if ((uint32_t)copy0 + copies > B.copies) B.copies = (uint32_t)copy0 + copies;
+  }
+  e.cw0 = B.cw;
+  B.cw += (nb + (1ull << P->chunk_log2) - 1) >> P->chunk_log2;
+  if (B.copies > P->hist_copies || B.cw > P->cw_cap) return LCP_ERR_ARG;
+  B.hb.push_back(enc_hist_blocks(nb));
+  B.cb.push_back(enc_chunk_blocks(nb, P->chunk_log2));
+  B.fb.push_back(enc_fixed_blocks(nb));
+  B.values += nb;
+  B.NA++;
   return LCP_OK;
 }
 
+lcp_status enc_launch(lcp_plan_s* P, EncBuild& B, uint8_t* out, uint64_t cap, bool hist_done,
+                      hipStream_t s) {
+  const int NA = B.NA;
+  EncLaunch L;
+  L.arrs = P->earr_dev;
+  L.recs = P->erec_dev;
+  L.pre = P->epre_dev;
+  L.NA = NA;
+  L.R = B.R;
+  uint32_t* ph = P->epre_host;
+  uint32_t* pc = ph + (NA + 1);
+  uint32_t* pf = pc + (NA + 1);
+  uint32_t h = 0, c = 0, f = 0;
+  for (int a = 0; a < NA; a++) {
+    ph[a] = h;
+    pc[a] = c;
+    pf[a] = f;
+    h += B.hb[a];
+    c += B.cb[a];
+    f += B.fb[a];
+  }
+  ph[NA] = h;
+  pc[NA] = c;
+  pf[NA] = f;
+  L.hist_blocks = h;
+  L.chunk_blocks = c;
+  L.fixed_blocks = f;
+  L.values = B.values;
+  lcp_status st = upload(P->earr_host, P->earr_dev, sizeof(EncArr) * NA, s);
+  if (!st) st = upload(P->erec_host, P->erec_dev, sizeof(EncRec) * B.R, s);
+  if (!st) st = upload(P->epre_host, P->epre_dev, sizeof(uint32_t) * 3 * (NA + 1), s);
+  if (st) return st;
+  launch_encode(L, P->chunk_log2, P->work, P->chunk_words, P->hist_part, P->hist_max,
+                P->huff_lens, P->huff_maxd, out, cap, P->offs_dev, P->err, hist_done, s);
+  return LCP_OK;
+}
+
+// Waits for the encode launch set: record offsets offs[0..R] (host) and the
+// device error word.
+lcp_status finish_records(lcp_plan_s* P, int R, uint64_t* offs, uint32_t* flags, hipStream_t s) {
+  lcp_status st = read_ret(P, 2 + (size_t)R, s);
+  if (st) return st;
+  if (g_timer_plan == P) timer_collect(P);
+  for (int r = 0; r <= R; r++) offs[r] = P->ret_host[1 + r];
+  if (flags) *flags = host_err(P);
+  if (host_err(P) & kErrCapacity) return LCP_ERR_CAPACITY;
+  return LCP_OK;
+}
+
+RecHdr make_hdr(int mode, int F, int k, int cl, int A, uint64_t n, uint64_t seq, uint64_t ref_seq,
+                const HostGrid* g) {
+  RecHdr h;
+  memset(&h, 0, sizeof(h));
+  h.mode = mode;
+  h.F = F;
+  h.k = k;
+  h.chunk_log2 = cl;
+  h.A = A;
+  h.n = n;
+  h.seq = seq;
+  h.ref_seq = ref_seq;
+  for (int f = 0; f < F; f++) {
+    h.m[f] = g[f].m;
+    h.eb_q[f] = g[f].eb_q;
+  }
+  return h;
+}
+
+// ------------------------------------------------------------------ LCP-S
+// LCP-S on R independent frames (seg_host[r].x / .n) in one set of launches.
+// g[r] are frame r's grids, hi[r] its maxima.  Records go back to back to out;
+// offs (host, R + 1) receives their offsets.  q_slot (R == 1 only) receives
+// the slot-order codes; perm_dst (nullable, R device pointers, each nullable)
+// the slot -> input permutations; *perm_res the batch's permutation array.
+lcp_status compress_s_batch(lcp_plan_s* P, int R, const HostGrid (*g)[kMaxF],
+                            const float (*hi)[kMaxF], int k, uint64_t seq0, uint8_t* out,
+                            uint64_t cap, int32_t* q_slot, uint32_t* const* perm_dst,
+                            uint64_t* offs, const uint32_t** perm_res, hipStream_t s) {
+  const int F = P->F;
+  if (R < 1 || R > P->RB || (q_slot && R != 1)) return LCP_ERR_ARG;
+  std::vector<int> kb(R);
+  std::vector<RecHdr> hdr(R);
+  for (int r = 0; r < R; r++) {
+    SegDev& sg = P->seg_host[r];
+    uint64_t bn[3];
+    unsigned __int128 tot = 1;
+    for (int f = 0; f < F; f++) {
+      int64_t qm = host_quant(hi[r][f], g[r][f]);
+      if (qm >= kQLimit) return LCP_ERR_RANGE;
+      if (f < 3) {
+        bn[f] = (uint64_t)((qm >> k) + 1);
+        tot *= bn[f];
+      }
+      sg.m[f] = g[r][f].m;
+      sg.eb_q[f] = g[r][f].eb_q;
+      sg.inv[f] = g[r][f].inv;
+    }
+    if (tot >= ((unsigned __int128)1 << 63)) return LCP_ERR_RANGE;
+    kb[r] = bitwidth64((uint64_t)tot - 1);
+    sg.bn0 = bn[0];
+    sg.bn1 = bn[1];
+    sg.k = k;
+    hdr[r] = make_hdr(0, F, k, P->chunk_log2, F + 2, sg.n, seq0 + r, ~0ull, g[r]);
+    for (int d = 0; d < 3; d++) hdr[r].bn[d] = (uint32_t)bn[d];
+  }
+  // Sort runs: consecutive frames whose tags fit above their block-id bits in
+  // 64-bit keys are sorted together (normally the whole batch).
+  struct Run {
+    int r0, r1;
+  };
+  std::vector<Run> runs;
+  int sort_bits = 0;
+  for (int r0 = 0; r0 < R;) {
+    int r1 = r0 + 1, kmax = kb[r0];
+    while (r1 < R) {
+      int km = kb[r1] > kmax ? kb[r1] : kmax;
+      if (km + bitwidth64((uint64_t)(r1 - r0)) > 64) break;
+      kmax = km;
+      r1++;
+    }
+    for (int r = r0; r < r1; r++) {
+      P->seg_host[r].key_hi = (r == r0) ? 0ull : ((uint64_t)(r - r0) << kmax);
+      P->seg_host[r].id_mask = kmax ? (~0ull >> (64 - kmax)) : 0ull;
+    }
+    int bits = kmax + bitwidth64((uint64_t)(r1 - r0 - 1));
+    sort_bits = bits > sort_bits ? bits : sort_bits;
+    runs.push_back({r0, r1});
+    r0 = r1;
+  }
+  SegLayout L;
+  lcp_status st = upload_segs(P, R, &L, s);
+  if (st) return st;
+  const uint64_t ntot = L.ntot;
+  const uint32_t* pre_1k = P->segpre_dev + (R + 1);
+  const uint32_t* pre_256 = P->segpre_dev + 2 * (R + 1);
+  launch_quant_key_b(P->seg_dev, pre_1k, L.blocks_1k, R, P->keys0, P->vals0, ntot, s);
+  int cur = 0;
+  uint32_t* tmp32 = reinterpret_cast<uint32_t*>(P->scan_tmp);
+  for (const Run& ru : runs) {
+    const uint64_t o = P->seg_host[ru.r0].off;
+    const uint64_t m = P->seg_host[ru.r1 - 1].off + P->seg_host[ru.r1 - 1].n - o;
+    cur = radix_sort(P->keys0 + o, P->vals0 + o, P->keys1 + o, P->vals1 + o, m, sort_bits,
+                     P->hist, tmp32, s);
+  }
+  const uint64_t* keys = cur ? P->keys1 : P->keys0;
+  const uint32_t* perm = cur ? P->vals1 : P->vals0;
+  launch_runs_b(keys, P->seg_dev, pre_1k, L.blocks_1k, R, ntot, P->flags, P->ids, P->starts,
+                P->rstart, P->Bs, tmp32, s);
+  launch_block_syms_b(P->ids, P->starts, P->rstart, R, P->seg_dev, ntot, P->v_id, P->v_cnt, s);
+  uint32_t* v_rel = P->v_slot;
+  uint32_t* v_sup = P->v_slot + 3 * ntot;
+  launch_slot_syms_b(P->seg_dev, pre_256, L.blocks_256, R, F, perm, ntot, v_rel, v_sup, q_slot, s);
+
+  EncBuild B;
+  B.R = R;
+  for (int r = 0; r < R; r++) {
+    const SegDev& sg = P->seg_host[r];
+    const uint64_t n = sg.n, o = sg.off;
+    EncRec& rc = P->erec_host[r];
+    memset(&rc, 0, sizeof(rc));
+    rc.h = hdr[r];
+    rc.B_dev = P->Bs + r;
+    rc.a0 = (uint32_t)B.NA;
+    if ((st = enc_add(P, B, ArrIn{P->v_id + o, 1, P->Bs + r, n}, n, r, -1, 0))) return st;
+    if ((st = enc_add(P, B, ArrIn{P->v_cnt + o, 1, P->Bs + r, n}, n, r, -1, 0))) return st;
+    for (int d = 0; d < 3; d++)
+      if ((st = enc_add(P, B, ArrIn{v_rel + (uint64_t)d * ntot + o, 0, nullptr, n}, n, r, -1, 0)))
+        return st;
+    for (int f = 3; f < F; f++)
+      if ((st = enc_add(P, B, ArrIn{v_sup + (uint64_t)(f - 3) * ntot + o, 0, nullptr, n}, n, r, -1, 0)))
+        return st;
+  }
+  launch_fill_u32(P->err, 1, 0u, s);
+  if ((st = enc_launch(P, B, out, cap, false, s))) return st;
+  if (perm_dst) {
+    bool any = false;
+    for (int r = 0; r < R; r++) {
+      P->permdst_host[r] = perm_dst[r];
+      any |= perm_dst[r] != nullptr;
+    }
+    if (any) {
+      if ((st = upload(P->permdst_host, P->permdst_dev, sizeof(uint32_t*) * R, s))) return st;
+      launch_copy_perm_b(perm, P->seg_dev, pre_1k, L.blocks_1k, R, P->permdst_dev, s);
+    }
+  }
+  if (perm_res) *perm_res = perm;
+  return finish_records(P, R, offs, nullptr, s);
+}
+
+// LCP-S on one frame (a batch of one).
 struct SResult {
   uint64_t size = 0;
   const uint32_t* perm = nullptr;  // device, slot -> input index
 };
 
-// LCP-S on one frame.  grids[] come from this frame's extent; hi[] its maxima.
 lcp_status compress_s(lcp_plan_s* P, const float* const* x, uint64_t n, const HostGrid* g,
                       const float* hi, int k, uint64_t seq, uint8_t* out, uint64_t cap,
                       int32_t* q_slot, SResult* res, hipStream_t s) {
-  const int F = P->F;
-  uint32_t bn[3];
-  unsigned __int128 tot = 1;
-  for (int f = 0; f < F; f++) {
-    int64_t qm = host_quant(hi[f], g[f]);
-    if (qm >= kQLimit) return LCP_ERR_RANGE;
-    if (f < 3) {
-      bn[f] = (uint32_t)((qm >> k) + 1);
-      tot *= bn[f];
-    }
-  }
-  if (tot >= ((unsigned __int128)1 << 63)) return LCP_ERR_RANGE;
-  const uint64_t total_blocks = (uint64_t)tot;
-  int bits = bitwidth64(total_blocks - 1);
+  for (int f = 0; f < P->F; f++) P->seg_host[0].x[f] = x[f];
+  P->seg_host[0].n = n;
+  HostGrid g1[1][kMaxF];
+  float h1[1][kMaxF];
+  memcpy(g1[0], g, sizeof(HostGrid) * P->F);
+  memcpy(h1[0], hi, sizeof(float) * P->F);
+  uint64_t offs[2] = {0, 0};
+  lcp_status st = compress_s_batch(P, 1, g1, h1, k, seq, out, cap, q_slot, nullptr, offs,
+                                   &res->perm, s);
+  res->size = offs[1];
+  return st;
+}
 
-  FieldPtrs fp;
-  memset(&fp, 0, sizeof(fp));
-  for (int f = 0; f < F; f++) fp.p[f] = x[f];
-  GridDev gd = to_dev(g, F);
-  launch_quant_key(fp, n, gd, k, bn[0], bn[1], P->keys0, P->vals0, s);
-  int cur = radix_sort(P->keys0, P->vals0, P->keys1, P->vals1, n, bits, P->hist,
-                       reinterpret_cast<uint32_t*>(P->scan_tmp), s);
-  uint64_t* keys = cur ? P->keys1 : P->keys0;
-  uint32_t* perm = cur ? P->vals1 : P->vals0;
-  uint32_t* B_dev = P->small;
-  launch_runs(keys, n, P->flags, P->ids, P->starts, B_dev,
-              reinterpret_cast<uint32_t*>(P->scan_tmp), s);
-  launch_block_syms(P->ids, P->starts, B_dev, n, P->v_id, P->v_cnt, s);
-  uint32_t* v_rel = P->v_slot;
-  uint32_t* v_sup = P->v_slot + 3 * n;
-  launch_slot_syms(fp, F, n, gd, k, perm, v_rel, v_sup, q_slot, s);
-
-  ArrSet set;
-  memset(&set, 0, sizeof(set));
-  set.A = F + 2;
-  set.a[0] = ArrIn{P->v_id, 1, B_dev, n};
-  set.a[1] = ArrIn{P->v_cnt, 1, B_dev, n};
-  for (int d = 0; d < 3; d++) set.a[2 + d] = ArrIn{v_rel + (uint64_t)d * n, 0, nullptr, n};
-  for (int f = 3; f < F; f++) set.a[2 + f] = ArrIn{v_sup + (uint64_t)(f - 3) * n, 0, nullptr, n};
-  RecHdr h;
-  memset(&h, 0, sizeof(h));
-  h.mode = 0;
-  h.F = F;
-  h.k = k;
-  h.chunk_log2 = P->chunk_log2;
-  h.A = F + 2;
-  h.n = n;
-  h.seq = seq;
-  h.ref_seq = ~0ull;
-  for (int d = 0; d < 3; d++) h.bn[d] = bn[d];
-  for (int f = 0; f < F; f++) {
-    h.m[f] = g[f].m;
-    h.eb_q[f] = g[f].eb_q;
-  }
-  HIP_OK(hipMemsetAsync(P->small + 1, 0, sizeof(uint32_t), s));
-  launch_encode(set, n, P->chunk_log2, P->work, P->chunk_words, P->max_chunks, P->hist_part,
-                P->hist_max, P->huff_lens, P->huff_maxd, h, B_dev, out,
-                cap, P->size_dev, P->small + 1, false, s);
-  res->perm = perm;
-  return finish_record(P, &res->size, nullptr, s);
+lcp_status extent(lcp_plan_s* P, const float* const* x, uint64_t n, float* lo, float* hi,
+                  hipStream_t s) {
+  for (int f = 0; f < P->F; f++) P->seg_host[0].x[f] = x[f];
+  P->seg_host[0].n = n;
+  float l1[1][kMaxF], h1[1][kMaxF];
+  lcp_status st = extent_batch(P, 1, l1, h1, s);
+  if (st) return st;
+  memcpy(lo, l1[0], sizeof(float) * P->F);
+  memcpy(hi, h1[0], sizeof(float) * P->F);
+  return LCP_OK;
 }
 
 // LCP-T on one frame against a resident reference.  Whether the frame fits the
@@ -339,32 +591,26 @@ lcp_status compress_t(lcp_plan_s* P, const float* const* x, uint64_t n, const Re
     gd.eb2[f] = 2.0 * ref.grid[f].eb;
     gd.lim[f] = ldexp(1.0, ref.grid[f].E);
   }
-  launch_fill_u32(P->small + 1, 1, 0u, s);
+  launch_fill_u32(P->err, 1, 0u, s);
   launch_t_resid(fp, F, n, gd, P->ppool[ref.perm], P->qpool[ref.q], P->v_slot, q_new,
-                 P->small + 1, P->hist_part, P->hist_max, s);
-  ArrSet set;
-  memset(&set, 0, sizeof(set));
-  set.A = F;
-  for (int f = 0; f < F; f++) set.a[f] = ArrIn{P->v_slot + (uint64_t)f * n, 0, nullptr, n};
-  RecHdr h;
-  memset(&h, 0, sizeof(h));
-  h.mode = 1;
-  h.F = F;
-  h.k = 0;
-  h.chunk_log2 = P->chunk_log2;
-  h.A = F;
-  h.n = n;
-  h.seq = seq;
-  h.ref_seq = ref.seq;
-  for (int f = 0; f < F; f++) {
-    h.m[f] = ref.grid[f].m;
-    h.eb_q[f] = ref.grid[f].eb_q;
-  }
-  launch_encode(set, n, P->chunk_log2, P->work, P->chunk_words, P->max_chunks, P->hist_part,
-                P->hist_max, P->huff_lens, P->huff_maxd, h, P->small,
-                out, cap, P->size_dev, P->small + 1, true, s);
+                 P->err, P->hist_part, P->hist_max, s);
+  EncBuild B;
+  B.R = 1;
+  EncRec& rc = P->erec_host[0];
+  memset(&rc, 0, sizeof(rc));
+  rc.h = make_hdr(1, F, 0, P->chunk_log2, F, n, seq, ref.seq, ref.grid);
+  rc.a0 = 0;
+  lcp_status st;
+  // the residual kernel counts field f into spread copies f * kHistCopies ...
+  for (int f = 0; f < F; f++)
+    if ((st = enc_add(P, B, ArrIn{P->v_slot + (uint64_t)f * n, 0, nullptr, n}, n, 0,
+                      f * kHistCopies, kHistCopies)))
+      return st;
+  if ((st = enc_launch(P, B, out, cap, true, s))) return st;
   uint32_t flags = 0;
-  lcp_status st = finish_record(P, size, &flags, s);
+  uint64_t offs[2] = {0, 0};
+  st = finish_records(P, 1, offs, &flags, s);
+  *size = offs[1];
   if (flags & kErrNonFinite) return LCP_ERR_ARG;
   if (flags & kErrRange) return LCP_ERR_RANGE;
   return st;
@@ -448,10 +694,17 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
   int qt_i = -1, qs_i = -1, ps_i = -1;
   uint64_t size_s = 0, size_t_ = 0;
   bool have_s = false, have_t = false;
+  // A frame decided T is coded straight into `out` when it can hold any record
+  // (a spatial fallback then goes to the spare buffer); otherwise the temporal
+  // candidate goes to the spare buffer and the spatial one to `out`.
+  const bool t_direct = decision == LCP_DECIDE_T && cap >= bound_bytes(F, n);
+  uint8_t* t_buf = t_direct ? out : P->rec_tmp;
+  uint8_t* s_buf = t_direct ? P->rec_tmp : out;
+  const uint64_t s_cap = t_direct ? P->rec_tmp_cap : cap;
   if (decision != LCP_DECIDE_S) {
     qt_i = free_q(P, -1);
-    st = compress_t(P, fr.fields, n, *ref, P->seq, P->rec_tmp, P->rec_tmp_cap, P->qpool[qt_i],
-                    &size_t_, s);
+    st = compress_t(P, fr.fields, n, *ref, P->seq, t_buf, t_direct ? cap : P->rec_tmp_cap,
+                    P->qpool[qt_i], &size_t_, s);
     if (st == LCP_OK) have_t = true;
     else if (st == LCP_ERR_RANGE && fr.method != LCP_METHOD_T) st = LCP_OK;  // T infeasible
     else return st;
@@ -472,7 +725,7 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
       qs_i = free_q(P, qt_i);
       ps_i = free_perm(P);
     }
-    st = compress_s(P, fr.fields, n, sg, hi, P->k, P->seq, out, cap,
+    st = compress_s(P, fr.fields, n, sg, hi, P->k, P->seq, s_buf, s_cap,
                     multi ? P->qpool[qs_i] : nullptr, &sr, s);
     if (st == LCP_ERR_CAPACITY && have_t && size_t_ < sr.size) {
       st = LCP_OK;  // the temporal record is the smaller one and may still fit
@@ -500,7 +753,10 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
     *size = chosen;
     return LCP_ERR_CAPACITY;
   }
-  if (chose_t) HIP_OK(hipMemcpyAsync(out, P->rec_tmp, size_t_, hipMemcpyDeviceToDevice, s));
+  if (chose_t && t_buf != out)
+    HIP_OK(hipMemcpyAsync(out, t_buf, size_t_, hipMemcpyDeviceToDevice, s));
+  if (!chose_t && s_buf != out)
+    HIP_OK(hipMemcpyAsync(out, s_buf, size_s, hipMemcpyDeviceToDevice, s));
   *size = chosen;
   if (used) *used = chose_t ? LCP_METHOD_T : LCP_METHOD_S;
   if (have_s) {
@@ -627,13 +883,114 @@ lcp_status decode_arrays(lcp_plan_s* P, int base, int A, int cl, uint64_t bytes,
     hb += decode_blocks(P->arrtab_host[base + a], cl, true);
     fb += decode_blocks(P->arrtab_host[base + a], cl, false);
   }
-  HIP_OK(hipMemcpyAsync(P->arrtab_dev + base, P->arrtab_host + base, sizeof(DecArr) * A,
-                        hipMemcpyHostToDevice, s));
-  HIP_OK(hipMemcpyAsync(P->prefix_dev + 2 * base, hp, sizeof(uint32_t) * 2 * A,
-                        hipMemcpyHostToDevice, s));
+  lcp_status st = upload(P->arrtab_host + base, P->arrtab_dev + base, sizeof(DecArr) * A, s);
+  if (!st) st = upload(hp, P->prefix_dev + 2 * base, sizeof(uint32_t) * 2 * A, s);
+  if (st) return st;
   launch_decode(P->arrtab_dev + base, A, P->prefix_dev + 2 * base, hb,
                 P->prefix_dev + 2 * base + A, fb, cl, bytes, P->lut + ((uint64_t)base << kMaxLen),
-                P->small + 1, s);
+                P->err, s);
+  return LCP_OK;
+}
+
+// Single-frame plans: spatial records j0..j1 decoded as one batch (slot and
+// block arrays concatenated, per-frame scans by rebasing batch-wide scans).
+lcp_status decompress_s_batch(lcp_plan_s* P, const ParsedHdr* H, const lcp_blob* blobs,
+                              const lcp_frame_out* outs, int R, hipStream_t s) {
+  const int F = P->F;
+  const int cl = H[0].cl;
+  uint64_t ntot = 0, Btot = 0, bytes = 0;
+  int A = 0;
+  uint32_t* ps = P->dpre_host;
+  uint32_t* pb = ps + (R + 1);
+  uint32_t bs = 0, bb = 0;
+  for (int r = 0; r < R; r++) {
+    const ParsedHdr& h = H[r];
+    unsigned __int128 tot = (unsigned __int128)h.bn[0] * h.bn[1] * h.bn[2];
+    if (h.bn[0] == 0 || h.bn[1] == 0 || h.bn[2] == 0 || tot >= ((unsigned __int128)1 << 63))
+      return LCP_ERR_CORRUPT;
+    DSegDev& g = P->dseg_host[r];
+    memset(&g, 0, sizeof(g));
+    for (int f = 0; f < F; f++) {
+      g.out[f] = outs[r].fields[f];
+      g.m[f] = h.m[f];
+      g.eb_q[f] = h.eb_q[f];
+    }
+    g.n = h.n;
+    g.off = ntot;
+    g.B = h.B;
+    g.boff = Btot;
+    g.total_blocks = (uint64_t)tot;
+    g.bn0 = h.bn[0];
+    g.bn1 = h.bn[1];
+    g.k = h.k;
+    ps[r] = bs;
+    pb[r] = bb;
+    bs += (uint32_t)((h.n + kSeg1k - 1) / kSeg1k);
+    bb += (uint32_t)((h.B + kSeg1k - 1) / kSeg1k);
+    ntot += h.n;
+    Btot += h.B;
+  }
+  ps[R] = bs;
+  pb[R] = bb;
+  // every array of every record in one decode launch set
+  for (int r = 0; r < R; r++) {
+    const ParsedHdr& h = H[r];
+    const DSegDev& g = P->dseg_host[r];
+    const uint8_t* rec = reinterpret_cast<const uint8_t*>(blobs[r].data);
+    for (int a = 0; a < h.A; a++) {
+      DecArr& d = P->arrtab_host[A++];
+      d.data = rec + h.aoff[a];
+      d.nbytes = h.anb[a];
+      d.n = h.an[a];
+      d.coder = h.coder[a];
+      d.param = h.param[a];
+      d.used = h.used[a];
+      if (a == 0) {
+        d.out = P->v_id + g.boff;
+        d.mode = 0;
+        d.limit = g.total_blocks;
+      } else if (a == 1) {
+        d.out = P->v_cnt + g.boff;
+        d.mode = 1;
+        d.limit = ~0ull;
+      } else {
+        const int f = a - 2;
+        d.out = P->v_slot + (uint64_t)f * ntot + g.off;
+        d.mode = 2;
+        d.limit = f < 3 ? (1ull << h.k) : (uint64_t)kQLimit;
+      }
+      bytes += h.anb[a] + (a < 2 ? 8 : 4) * h.an[a];
+    }
+  }
+  lcp_status st = upload(P->dseg_host, P->dseg_dev, sizeof(DSegDev) * R, s);
+  if (!st) st = upload(P->dpre_host, P->dpre_dev, sizeof(uint32_t) * 2 * (R + 1), s);
+  if (!st) st = decode_arrays(P, 0, A, cl, bytes, s);
+  if (st) return st;
+  const uint32_t* pre_slot = P->dpre_dev;
+  const uint32_t* pre_blk = P->dpre_dev + (R + 1);
+  uint64_t* ids = P->v_id;
+  uint64_t* cnt = P->v_cnt;
+  uint64_t* cum = P->ids;
+  // ids and counts: per-frame inclusive scans; slot ends: batch-wide scan of counts
+  scan_device<uint64_t>(ids, Btot, nullptr, false, P->scan_tmp, s);
+  seg_rebase<uint64_t>(ids, 0, 1, P->dseg_dev, pre_blk, bb, R, true,
+                       reinterpret_cast<uint64_t*>(P->segbase), s);
+  scan_device<uint64_t>(cnt, Btot, nullptr, false, P->scan_tmp, s);
+  seg_rebase<uint64_t>(cnt, 0, 1, P->dseg_dev, pre_blk, bb, R, true,
+                       reinterpret_cast<uint64_t*>(P->segbase), s);
+  HIP_OK(hipMemcpyAsync(cum, cnt, Btot * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+  scan_device<uint64_t>(cum, Btot, nullptr, false, P->scan_tmp, s);
+  launch_fill_u32(P->flags, ntot, 0u, s);
+  launch_s_blocks_b(ids, cnt, cum, P->dseg_dev, pre_blk, bb, R, Btot, ntot, P->corner, P->flags,
+                    P->err, s);
+  uint32_t* tmp32 = reinterpret_cast<uint32_t*>(P->scan_tmp);
+  scan_device<uint32_t>(P->flags, ntot, nullptr, false, tmp32, s);
+  for (int d = 0; d < 3; d++)
+    scan_device<uint32_t>(P->v_slot + (uint64_t)d * ntot, ntot, nullptr, false, tmp32, s);
+  seg_rebase<uint32_t>(P->v_slot, ntot, 3, P->dseg_dev, pre_slot, bs, R, false,
+                       reinterpret_cast<uint32_t*>(P->segbase), s);
+  launch_s_recon_b(P->flags, P->corner, P->v_slot, P->dseg_dev, pre_slot, bs, R, F, Btot, ntot,
+                   P->err, s);
   return LCP_OK;
 }
 
@@ -650,7 +1007,10 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
     P->blobtab_host[2 * j] = (uint64_t)(uintptr_t)blobs[j].data;
     P->blobtab_host[2 * j + 1] = blobs[j].size;
   }
-  HIP_OK(hipMemcpyAsync(P->blobtab_dev, P->blobtab_host, 16 * nf, hipMemcpyHostToDevice, s));
+  {
+    lcp_status st = upload(P->blobtab_host, P->blobtab_dev, 16 * nf, s);
+    if (st) return st;
+  }
   launch_gather_headers(P->blobtab_dev, (int)nf, kHdrStage, P->hdr_dev, s);
   HIP_OK(hipMemcpyAsync(P->hdr_host, P->hdr_dev, (size_t)kHdrStage * nf, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
@@ -687,8 +1047,18 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
       if (h.mode == 0 && first_in_batch(P, h.seq)) sa = r;
     }
   }
+  launch_fill_u32(P->err, 1, 0u, s);
+  if (!multi) {
+    // independent spatial records: batches of at most NB particles
+    for (uint64_t j0 = 0; j0 < nf;) {
+      uint64_t j1 = j0, tot = 0;
+      while (j1 < nf && tot + H[j1].n <= P->NB && (j1 == j0 || H[j1].cl == H[j0].cl)) tot += H[j1++].n;
+      lcp_status st = decompress_s_batch(P, &H[j0], blobs + j0, outs + j0, (int)(j1 - j0), s);
+      if (st) return st;
+      j0 = j1;
+    }
+  } else {
   // ---- entropy decoding of every array that lands in the output buffers
-  launch_fill_u32(P->small + 1, 1, 0u, s);
   int A = 0;
   uint64_t bytes = 0;
   int cl = nf ? H[0].cl : 10;
@@ -782,21 +1152,24 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
       scan_device<uint64_t>(cum, B, nullptr, false, P->scan_tmp, s);
       launch_fill_u32(P->flags, n, 0u, s);
       launch_s_blocks(ids, cnt, cum, B, n, total_blocks, h.bn, h.k, P->corner, P->flags,
-                      P->small + 1, s);
+                      P->err, s);
       uint32_t* tmp32 = reinterpret_cast<uint32_t*>(P->scan_tmp);
       scan_device<uint32_t>(P->flags, n, nullptr, false, tmp32, s);
       for (int d = 0; d < 3; d++)
         scan_device<uint32_t>(reinterpret_cast<uint32_t*>(outs[j].fields[d]), n, nullptr, false,
                               tmp32, s);
-      launch_s_recon(P->flags, P->corner, B, F, n, h.k, gd, op, q_slot, P->small + 1, s);
+      launch_s_recon(P->flags, P->corner, B, F, n, h.k, gd, op, q_slot, P->err, s);
     } else {
-      launch_t_recon(P->dqpool[refq[j]], F, n, gd, op, q_slot, P->small + 1, s);
+      launch_t_recon(P->dqpool[refq[j]], F, n, gd, op, q_slot, P->err, s);
     }
   }
-  HIP_OK(hipMemcpyAsync(P->host_small + 1, P->small + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-  HIP_OK(hipStreamSynchronize(s));
+  }
+  {
+    lcp_status st = read_ret(P, 1, s);
+    if (st) return st;
+  }
   if (g_timer_plan == P) timer_collect(P);
-  if (P->host_small[1] & kErrCorrupt) return LCP_ERR_CORRUPT;
+  if (host_err(P) & kErrCorrupt) return LCP_ERR_CORRUPT;
   if (multi) {
     P->dprev = sp;
     P->danchor = sa;
@@ -804,43 +1177,70 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
   return LCP_OK;
 }
 
+template <typename T>
+lcp_status halloc(T** out, size_t elems) {
+  return hipHostMalloc((void**)out, (elems ? elems : 1) * sizeof(T), 0) == hipSuccess ? LCP_OK
+                                                                                    : LCP_ERR_DEVICE;
+}
+
 lcp_status alloc_plan(lcp_plan_s* P) {
-  const uint64_t N = P->N;
-  const int F = P->F;
-  const uint64_t ntiles = (N + 4095) / 4096;
+  const uint64_t N = P->N, NB = P->NB;
+  const int F = P->F, RB = P->RB;
+  const uint64_t ntiles = (NB + 4095) / 4096;
+  P->NAmax = RB * (F + 2);
+  const uint64_t NA = (uint64_t)P->NAmax;
+  // spread histogram copies: enc_hist_copies(n) <= 1 + (1 + n / 8192) / 16 per
+  // array; the residual kernel uses kHistCopies per field
+  uint64_t hc = 2 * NA + (uint64_t)(F + 2) * NB / 131072 + 1;
+  if (hc > NA * kHistCopies) hc = NA * kHistCopies;
+  if (hc < (uint64_t)kMaxF * kHistCopies) hc = (uint64_t)kMaxF * kHistCopies;
+  P->hist_copies = hc;
+  P->cw_cap = (uint64_t)(F + 2) * NB / (1ull << P->chunk_log2) + NA + 1;
   lcp_status st;
 #define A_(ptr, cnt) \
   if ((st = dalloc(P, &(ptr), (cnt)))) return st
-  A_(P->keys0, N);
-  A_(P->keys1, N);
-  A_(P->ids, N);
-  A_(P->v_id, N);
-  A_(P->v_cnt, N);
-  A_(P->vals0, N);
-  A_(P->vals1, N);
+  A_(P->keys0, NB);
+  A_(P->keys1, NB);
+  A_(P->ids, NB);
+  A_(P->v_id, NB);
+  A_(P->v_cnt, NB);
+  A_(P->vals0, NB);
+  A_(P->vals1, NB);
   A_(P->hist, 256 * ntiles);
-  A_(P->flags, N);
-  A_(P->starts, N);
-  A_(P->v_slot, (uint64_t)F * N);
-  P->max_chunks = (N + (1ull << P->chunk_log2) - 1) >> P->chunk_log2;
-  A_(P->chunk_words, (uint64_t)kMaxArrays * P->max_chunks + 1);
+  A_(P->flags, NB);
+  A_(P->starts, NB);
+  A_(P->v_slot, (uint64_t)F * NB);
+  A_(P->chunk_words, P->cw_cap);
   A_(P->lut, (uint64_t)(kMaxBatchArrays + 2 * kMaxBatchFrames) << kMaxLen);
-  A_(P->ext_part, 2 * kMaxF * 256);
-  A_(P->hist_part, (uint64_t)kMaxArrays * kHistCopies * kAlphabet);
-  A_(P->hist_max, (uint64_t)kMaxArrays * kHistCopies);
-  A_(P->huff_lens, (uint64_t)kMaxArrays * kHuffCandidates * kAlphabet);
-  A_(P->huff_maxd, (uint64_t)kMaxArrays * kHuffCandidates);
+  A_(P->ext_part, (uint64_t)2 * kMaxF * kSegExtCap * RB);
+  A_(P->hist_part, hc * kAlphabet);
+  A_(P->hist_max, hc);
+  A_(P->huff_lens, NA * kHuffCandidates * kAlphabet);
+  A_(P->huff_maxd, NA * kHuffCandidates);
   A_(P->hdr_dev, (uint64_t)kHdrStage * kMaxBatchFrames);
   A_(P->blobtab_dev, 2 * kMaxBatchFrames);
   A_(P->arrtab_dev, kMaxBatchArrays + 2 * kMaxBatchFrames);
   A_(P->prefix_dev, 2 * (kMaxBatchArrays + 2 * kMaxBatchFrames));
-  A_(P->corner, 3 * N);
-  uint64_t sn = N > 256 * ntiles ? N : 256 * ntiles;
+  A_(P->corner, 3 * NB);
+  uint64_t sn = NB > 256 * ntiles ? NB : 256 * ntiles;
   P->scan_tmp_n = scan_tmp_elems(sn);
   A_(P->scan_tmp, P->scan_tmp_n);
-  A_(P->work, kMaxArrays);
-  A_(P->small, 64);
-  A_(P->size_dev, 1);
+  A_(P->work, NA);
+  A_(P->ret_dev, 2 + (uint64_t)RB + (uint64_t)RB * F);
+  P->err = reinterpret_cast<uint32_t*>(P->ret_dev);
+  P->offs_dev = P->ret_dev + 1;
+  P->ext_dev = reinterpret_cast<uint32_t*>(P->ret_dev + 2 + RB);
+  A_(P->seg_dev, RB);
+  A_(P->segpre_dev, 3 * ((uint64_t)RB + 1));
+  A_(P->rstart, (uint64_t)RB + 1);
+  A_(P->Bs, RB);
+  A_(P->permdst_dev, RB);
+  A_(P->dseg_dev, kMaxBatchFrames);
+  A_(P->dpre_dev, 2 * (kMaxBatchFrames + 1));
+  A_(P->segbase, 3 * kMaxBatchFrames);
+  A_(P->earr_dev, NA);
+  A_(P->erec_dev, RB);
+  A_(P->epre_dev, 3 * (NA + 1));
   P->rec_tmp_cap = bound_bytes(F, N);
   A_(P->rec_tmp, P->rec_tmp_cap);
   if (P->p.multi_frame) {
@@ -849,26 +1249,36 @@ lcp_status alloc_plan(lcp_plan_s* P) {
     for (int i = 0; i < 3; i++) A_(P->dqpool[i], (uint64_t)F * N);
   }
 #undef A_
-  if (hipMemset(P->hist_part, 0, sizeof(uint32_t) * kMaxArrays * kHistCopies * kAlphabet) != hipSuccess ||
-      hipMemset(P->hist_max, 0, sizeof(unsigned long long) * kMaxArrays * kHistCopies) != hipSuccess)
+  if (hipMemset(P->hist_part, 0, sizeof(uint32_t) * hc * kAlphabet) != hipSuccess ||
+      hipMemset(P->hist_max, 0, sizeof(unsigned long long) * hc) != hipSuccess)
     return LCP_ERR_DEVICE;
-  if (hipHostMalloc((void**)&P->host_small, 64 * sizeof(uint32_t), 0) != hipSuccess)
-    return LCP_ERR_DEVICE;
-  if (hipHostMalloc((void**)&P->host_size, sizeof(unsigned long long), 0) != hipSuccess)
-    return LCP_ERR_DEVICE;
-  if (hipHostMalloc((void**)&P->hdr_host, (size_t)kHdrStage * kMaxBatchFrames, 0) != hipSuccess ||
-      hipHostMalloc((void**)&P->blobtab_host, 16 * kMaxBatchFrames, 0) != hipSuccess ||
-      hipHostMalloc((void**)&P->arrtab_host, sizeof(DecArr) * (kMaxBatchArrays + 2 * kMaxBatchFrames), 0) != hipSuccess ||
-      hipHostMalloc((void**)&P->prefix_host, 8 * (kMaxBatchArrays + 2 * kMaxBatchFrames), 0) != hipSuccess)
-    return LCP_ERR_DEVICE;
+#define H_(ptr, cnt) \
+  if ((st = halloc(&(ptr), (cnt)))) return st
+  H_(P->ret_host, 2 + (size_t)RB + (size_t)RB * F);
+  H_(P->hdr_host, (size_t)kHdrStage * kMaxBatchFrames);
+  H_(P->blobtab_host, 2 * kMaxBatchFrames);
+  H_(P->arrtab_host, kMaxBatchArrays + 2 * kMaxBatchFrames);
+  H_(P->prefix_host, 2 * (kMaxBatchArrays + 2 * kMaxBatchFrames));
+  H_(P->seg_host, RB);
+  H_(P->segpre_host, 3 * ((size_t)RB + 1));
+  H_(P->permdst_host, RB);
+  H_(P->dseg_host, kMaxBatchFrames);
+  H_(P->dpre_host, 2 * (kMaxBatchFrames + 1));
+  H_(P->earr_host, NA);
+  H_(P->erec_host, RB);
+  H_(P->epre_host, 3 * (NA + 1));
+#undef H_
+  memset(P->seg_host, 0, sizeof(SegDev) * RB);
   return LCP_OK;
 }
 
 void free_plan(lcp_plan_s* P) {
   for (void* p : P->allocs) (void)hipFree(p);
-  if (P->host_small) (void)hipHostFree(P->host_small);
-  if (P->host_size) (void)hipHostFree(P->host_size);
-  for (void* hp : {(void*)P->hdr_host, (void*)P->blobtab_host, (void*)P->arrtab_host, (void*)P->prefix_host})
+  for (void* hp : {(void*)P->ret_host, (void*)P->hdr_host, (void*)P->blobtab_host,
+                   (void*)P->arrtab_host, (void*)P->prefix_host, (void*)P->seg_host,
+                   (void*)P->segpre_host, (void*)P->permdst_host, (void*)P->earr_host,
+                   (void*)P->erec_host, (void*)P->epre_host, (void*)P->dseg_host,
+                   (void*)P->dpre_host})
     if (hp) (void)hipHostFree(hp);
   for (auto e : P->ev_free) (void)hipEventDestroy(e);
   for (auto& pr : P->ev_pending) {
@@ -925,6 +1335,34 @@ lcp_status search_k(lcp_plan_s* P, const float* const* sample, uint64_t sn, hipS
   return LCP_OK;
 }
 
+// Single-frame plans: R independent frames through one extent pass and one
+// LCP-S launch set.  offs (host, R + 1) receives the records' offsets from out.
+lcp_status compress_group(lcp_plan_s* P, int R, const lcp_frame_in* fr, uint8_t* out,
+                          uint64_t cap, uint64_t* offs, uint32_t* const* perms, hipStream_t s) {
+  const int F = P->F;
+  for (int r = 0; r < R; r++) {
+    for (int f = 0; f < F; f++) P->seg_host[r].x[f] = fr[r].fields[f];
+    P->seg_host[r].n = fr[r].n;
+  }
+  std::vector<float> lo((size_t)R * kMaxF), hi((size_t)R * kMaxF);
+  float(*lo2)[kMaxF] = reinterpret_cast<float(*)[kMaxF]>(lo.data());
+  float(*hi2)[kMaxF] = reinterpret_cast<float(*)[kMaxF]>(hi.data());
+  lcp_status st = extent_batch(P, R, lo2, hi2, s);
+  if (st) return st;
+  std::vector<HostGrid> g((size_t)R * kMaxF);
+  HostGrid(*g2)[kMaxF] = reinterpret_cast<HostGrid(*)[kMaxF]>(g.data());
+  for (int r = 0; r < R; r++) {
+    double eb[kMaxF];
+    if ((st = field_eb(P->p, F, lo2[r], hi2[r], eb))) return st;
+    for (int f = 0; f < F; f++)
+      if ((st = make_grid(lo2[r][f], hi2[r][f], eb[f], &g2[r][f]))) return st;
+  }
+  st = compress_s_batch(P, R, g2, hi2, P->k, P->seq, out, cap, nullptr, perms, offs, nullptr, s);
+  if (st) return st;
+  P->seq += (uint64_t)R;
+  return LCP_OK;
+}
+
 }  // namespace
 
 namespace lcp {
@@ -971,7 +1409,10 @@ lcp_status lcp_plan(const lcp_params* params, const float* const* sample_fields,
   int cl = p.chunk_log2 == 0 ? 10 : p.chunk_log2;
   if (p.n_fields < 3 || p.n_fields > LCP_MAX_FIELDS || cl < 5 || cl > 12 || p.batch_size < 0 ||
       p.block_log2 < -1 || p.block_log2 > 16 || p.max_particles == 0 ||
-      p.max_particles > (1ull << 31) || !(p.eb > 0) || p.eb_mode < 0 || p.eb_mode > 2)
+      p.max_particles > (1ull << 31) || !(p.eb > 0) || p.eb_mode < 0 || p.eb_mode > 2 ||
+      p.max_batch_frames < 0 || p.max_batch_frames > kMaxBatch ||
+      (p.max_batch_particles != 0 &&
+       (p.max_batch_particles < p.max_particles || p.max_batch_particles > 0xFFFFFFFFull)))
     return LCP_ERR_ARG;
   if (p.block_log2 == -1 && (!sample_fields || sample_n == 0)) return LCP_ERR_ARG;
   if (hipSetDevice(p.device) != hipSuccess) return LCP_ERR_DEVICE;
@@ -981,6 +1422,13 @@ lcp_status lcp_plan(const lcp_params* params, const float* const* sample_fields,
   P->chunk_log2 = cl;
   P->F = p.n_fields;
   P->N = p.max_particles;
+  if (p.multi_frame) {
+    P->RB = 1;
+    P->NB = P->N;
+  } else {
+    P->RB = p.max_batch_frames == 0 ? 64 : p.max_batch_frames;
+    P->NB = p.max_batch_particles == 0 ? P->N : p.max_batch_particles;
+  }
   P->k = p.block_log2 < 0 ? 0 : p.block_log2;
   lcp_status st = alloc_plan(P);
   if (!st && p.block_log2 == -1) {
@@ -1031,6 +1479,40 @@ lcp_status lcp_compress(lcp_plan_t plan, uint64_t n_frames, const lcp_frame_in* 
   uint8_t* o = reinterpret_cast<uint8_t*>(out);
   uint64_t off = 0;
   out_offsets[0] = 0;
+  if (!plan->p.multi_frame) {
+    // independent frames: batches of up to RB frames and NB particles
+    std::vector<uint64_t> offs((size_t)plan->RB + 1);
+    for (uint64_t j = 0; j < n_frames;) {
+      int R = 0;
+      uint64_t tot = 0;
+      while (j + R < n_frames && R < plan->RB) {
+        const lcp_frame_in& fr = frames[j + R];
+        if (fr.n == 0 || fr.n > plan->N || fr.method < 0 || fr.method > 2) return LCP_ERR_ARG;
+        for (int f = 0; f < plan->F; f++)
+          if (!fr.fields[f]) return LCP_ERR_ARG;
+        if (fr.method == LCP_METHOD_T) return LCP_ERR_NO_REFERENCE;
+        if (tot + fr.n > plan->NB) break;
+        tot += fr.n;
+        R++;
+      }
+      uint64_t cap = out_cap > off ? out_cap - off : 0;
+      lcp_status st = compress_group(plan, R, frames + j, o + off, cap, offs.data(),
+                                     perms ? perms + j : nullptr, stream);
+      if (st == LCP_ERR_CAPACITY) {
+        for (int r = 0; r < R; r++) out_offsets[j + r + 1] = off + offs[r + 1];
+        return st;
+      }
+      if (st) return st;
+      for (int r = 0; r < R; r++) {
+        if (methods_used) methods_used[j + r] = LCP_METHOD_S;
+        out_offsets[j + r + 1] = off + offs[r + 1];
+      }
+      off += offs[R];
+      j += (uint64_t)R;
+    }
+    timer_collect(plan);
+    return LCP_OK;
+  }
   for (uint64_t j = 0; j < n_frames; j++) {
     uint64_t size = 0;
     int used = 0;

@@ -33,11 +33,6 @@ struct ArrIn {
   const uint32_t* n_dev;
   uint64_t n;
 };
-struct ArrSet {
-  ArrIn a[kMaxArrays];
-  int A;
-};
-
 // Per-array coder workspace in device memory.
 struct ArrWork {
   uint32_t hist[kAlphabet];
@@ -55,6 +50,58 @@ struct RecHdr {
   uint32_t bn[3];
   float m[kMaxF], eb_q[kMaxF];
 };
+
+// Encoder tables (device memory).  One launch set codes every array of every
+// record of a call; workgroups find their array through per-launch prefix
+// tables of workgroup counts (binary search), as the decoder does.
+struct EncArr {
+  ArrIn in;
+  uint32_t rec;     // record of the call the array belongs to
+  uint32_t copy0;   // first of its spread histogram copies in hist_part
+  uint32_t copies;  // number of spread copies
+  uint32_t pad;
+  uint64_t cw0;     // first of its chunk word counts in chunk_words
+};
+struct EncRec {
+  RecHdr h;
+  const uint32_t* B_dev;  // spatial records: the block count (device)
+  uint32_t a0, pad;       // first array of the record
+  unsigned long long size, off;  // written by the layout kernel
+};
+// Workgroups given to an array of (at most) n values in each encode launch, and
+// its spread histogram copies.
+uint32_t enc_hist_blocks(uint64_t n);
+uint32_t enc_hist_copies(uint64_t n);
+uint32_t enc_chunk_blocks(uint64_t n, int chunk_log2);
+uint32_t enc_fixed_blocks(uint64_t n);
+
+// One frame of a spatial batch (device table).  Frames are concatenated: frame
+// r owns slots [off, off + n) of every batch-wide array.  Per-particle kernels
+// give each frame whole workgroups (first workgroup from a prefix table).
+struct SegDev {
+  const float* x[kMaxF];
+  float m[kMaxF], eb_q[kMaxF];
+  double inv[kMaxF];
+  uint64_t n, off;
+  uint64_t bn0, bn1;  // Eq. 6 block grid
+  uint64_t key_hi;    // frame tag placed above the block-id bits of its sort keys
+  uint64_t id_mask;   // block-id bits of a key
+  int k, pad;
+};
+// One frame of a spatial decode batch (device table): frame r owns slots
+// [off, off + n) and blocks [boff, boff + B) of the batch-wide arrays.
+struct DSegDev {
+  float* out[kMaxF];
+  float m[kMaxF], eb_q[kMaxF];
+  uint64_t n, off, B, boff, total_blocks;
+  uint64_t bn0, bn1;
+  int k, pad;
+};
+constexpr int kMaxBatch = 1024;       // frames per spatial batch
+constexpr uint32_t kSegExtCap = 256;  // extent workgroups per frame (at most)
+constexpr uint32_t kSeg1k = 1024;     // slots per workgroup, element-wise kernels
+constexpr uint32_t kSeg256 = 256;     // slots per workgroup, slot symbol kernel
+uint32_t seg_ext_blocks(uint64_t n);
 
 // One array of a record being decoded.
 struct DecArr {
@@ -90,12 +137,30 @@ void ktimer_end(hipStream_t s, uint64_t bytes);
   } while (0)
 
 // ---- kernels_core.hip ----
-// Per-field extent as sortable keys ext[2f] (min), ext[2f+1] (max); part holds
-// 2 * F * 256 partials; err gets kErrNonFinite for NaN/Inf input (it is not cleared).
-void launch_extent(const FieldPtrs& x, int F, uint64_t n, uint32_t* ext, uint32_t* part,
-                   uint32_t* err, hipStream_t s);
-void launch_quant_key(const FieldPtrs& x, uint64_t n, const GridDev& g, int k, uint64_t bn0,
-                      uint64_t bn1, uint64_t* keys, uint32_t* vals, hipStream_t s);
+// Spatial batch front end.  pre_* are device prefix tables (R + 1 entries) of
+// the workgroups each frame gets: seg_ext_blocks(n), ceil(n / kSeg1k) and
+// ceil(n / kSeg256).  ext receives R x 2F sortable keys (min, max per field).
+void launch_extent_b(const SegDev* S, const uint32_t* pre_ext, uint32_t ext_blocks, int R, int F,
+                     uint32_t* ext, uint32_t* part, uint32_t* err, uint64_t bytes, hipStream_t s);
+void launch_quant_key_b(const SegDev* S, const uint32_t* pre_1k, uint32_t blocks, int R,
+                        uint64_t* keys, uint32_t* vals, uint64_t ntot, hipStream_t s);
+// Non-empty blocks of every frame: ids (frame tag removed), global start slots,
+// rstart[r] (first block of frame r; rstart[R] = all blocks) and Bs[r].
+void launch_runs_b(const uint64_t* keys, const SegDev* S, const uint32_t* pre_1k, uint32_t blocks,
+                   int R, uint64_t ntot, uint32_t* flags_scan, uint64_t* ids, uint32_t* starts,
+                   uint32_t* rstart, uint32_t* Bs, uint32_t* tmp32, hipStream_t s);
+// Block symbols of frame r go to v_id / v_cnt + S[r].off.
+void launch_block_syms_b(const uint64_t* ids, const uint32_t* starts, const uint32_t* rstart,
+                         int R, const SegDev* S, uint64_t ntot, uint64_t* v_id, uint64_t* v_cnt,
+                         hipStream_t s);
+// v_rel: [3][ntot], v_sup: [F-3][ntot]; q_slot (nullable): [F][ntot].
+void launch_slot_syms_b(const SegDev* S, const uint32_t* pre_256, uint32_t blocks, int R, int F,
+                        const uint32_t* perm, uint64_t ntot, uint32_t* v_rel, uint32_t* v_sup,
+                        int32_t* q_slot, hipStream_t s);
+// dst[r] (device table of device pointers, entries may be null) <- perm slice of frame r.
+void launch_copy_perm_b(const uint32_t* perm, const SegDev* S, const uint32_t* pre_1k,
+                        uint32_t blocks, int R, uint32_t* const* dst, hipStream_t s);
+
 // Stable LSD radix sort of (key, value) by the low `bits` key bits.  Returns the
 // buffer index (0: k0/v0, 1: k1/v1) that holds the result.
 int radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint64_t n, int bits,
@@ -104,13 +169,20 @@ template <typename T>
 void scan_device(T* data, uint64_t n, const uint32_t* n_dev, bool exclusive, T* tmp,
                  hipStream_t s);
 size_t scan_tmp_elems(uint64_t n);
-void launch_runs(const uint64_t* keys, uint64_t n, uint32_t* flags_scan, uint64_t* ids,
-                 uint32_t* starts, uint32_t* B_dev, uint32_t* tmp32, hipStream_t s);
-void launch_block_syms(const uint64_t* ids, const uint32_t* starts, const uint32_t* B_dev,
-                       uint64_t n, uint64_t* v_id, uint64_t* v_cnt, hipStream_t s);
-void launch_slot_syms(const FieldPtrs& x, int F, uint64_t n, const GridDev& g, int k,
-                      const uint32_t* perm, uint32_t* v_rel, uint32_t* v_sup, int32_t* q_slot,
-                      hipStream_t s);
+// Spatial batch decode.  seg_rebase turns batch-wide inclusive scans of nd
+// arrays (X + d * stride) into per-frame ones (segments by slot or, with
+// by_block, by block; pre: ceil(len / kSeg1k) workgroups per frame; bases:
+// nd * R scratch values).
+template <typename T>
+void seg_rebase(T* X, uint64_t stride, int nd, const DSegDev* D, const uint32_t* pre,
+                uint32_t blocks, int R, bool by_block, T* bases, hipStream_t s);
+void launch_s_blocks_b(const uint64_t* ids, const uint64_t* cnt, const uint64_t* cum,
+                       const DSegDev* D, const uint32_t* pre_blk, uint32_t blocks, int R,
+                       uint64_t Btot, uint64_t ntot, uint32_t* corner, uint32_t* mark,
+                       uint32_t* err, hipStream_t s);
+void launch_s_recon_b(const uint32_t* blk, const uint32_t* corner, const uint32_t* v,
+                      const DSegDev* D, const uint32_t* pre_slot, uint32_t blocks, int R, int F,
+                      uint64_t Btot, uint64_t ntot, uint32_t* err, hipStream_t s);
 // LCP-T residuals; err gets kErrNonFinite / kErrRange when the frame cannot be
 // coded on the reference grid.
 // The residual symbols of field f are also counted into array f's spread
@@ -131,25 +203,43 @@ void launch_s_recon(const uint32_t* blk, const uint32_t* corner, uint64_t B, int
 // out.p[f] holds int32 residuals; q_slot receives q_ref + residual.
 void launch_t_recon(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,
                     const OutPtrs& out, int32_t* q_slot, uint32_t* err, hipStream_t s);
+// Copies `bytes` (a multiple of 4) from host memory to device memory through
+// kernel arguments, kInstallWords words per launch (the host buffer may be
+// reused as soon as this returns).
+constexpr int kInstallWords = 512;
+void launch_install(const void* src, void* dst, size_t bytes, hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 // tab: nrec (device pointer, byte size) pairs; dst: nrec * stage bytes.
 void launch_gather_headers(const uint64_t* tab, int nrec, int stage, uint8_t* dst, hipStream_t s);
 void launch_copy_perm(const uint32_t* src, uint32_t* dst, uint64_t n, hipStream_t s);
 
 // ---- kernels_codec.hip ----
-// Workgroups per array in the histogram pass; their counts meet in kHistCopies
-// spread copies per array (hist_part: kMaxArrays * kHistCopies * kAlphabet u32,
-// hist_max: kMaxArrays * kHistCopies u64), zero between uses.
+// Workgroups per array in the histogram pass (at most); their counts meet in
+// up to kHistCopies spread copies per array (hist_part: kAlphabet u32 per copy,
+// hist_max: one u64 per copy), zero between uses.
 constexpr int kHistBlocks = 1024;
 constexpr int kHistCopies = 32;
-// Candidate halving counts built side by side (huff_lens: kMaxArrays * 32 *
-// kAlphabet bytes, huff_maxd: kMaxArrays * 32 u32).
+// Candidate halving counts built side by side (huff_lens: arrays * 32 *
+// kAlphabet bytes, huff_maxd: arrays * 32 u32).
 constexpr int kHuffCandidates = 32;
-void launch_encode(const ArrSet& set, uint64_t max_n, int chunk_log2, ArrWork* work,
-                   uint32_t* chunk_words, uint64_t max_chunks, uint32_t* hist_part,
-                   unsigned long long* hist_max, uint8_t* huff_lens, uint32_t* huff_maxd,
-                   const RecHdr& h, const uint32_t* B_dev, uint8_t* out, uint64_t cap,
-                   unsigned long long* size_dev, uint32_t* err, bool hist_done, hipStream_t s);
+// One encode launch set: NA arrays of R records (tables in device memory);
+// pre_dev holds three prefix tables of NA + 1 workgroup counts (histogram,
+// chunk, fixed-length pack), whose totals are given.  Records are placed back
+// to back at out + offs[r] (offs: R + 1 device values, offs[R] = total bytes);
+// a total beyond cap sets kErrCapacity and nothing is packed.  With hist_done
+// the histograms are already in the spread copies.
+struct EncLaunch {
+  const EncArr* arrs;
+  EncRec* recs;
+  const uint32_t* pre;
+  int NA, R;
+  uint32_t hist_blocks, chunk_blocks, fixed_blocks;
+  uint64_t values;  // sum of the arrays' lengths (bounds), for the kernel timer
+};
+void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, uint32_t* chunk_words,
+                   uint32_t* hist_part, unsigned long long* hist_max, uint8_t* huff_lens,
+                   uint32_t* huff_maxd, uint8_t* out, uint64_t cap, unsigned long long* offs,
+                   uint32_t* err, bool hist_done, hipStream_t s);
 // Workgroups needed by one array in the Huffman (huff=true) or fixed-length
 // decode launch (0 when the array uses the other coder).
 uint32_t decode_blocks(const DecArr& d, int chunk_log2, bool huff);
