@@ -173,6 +173,137 @@ def bench_batched(args, torch, lcp, datagen, dev):
     }
 
 
+def served_frames(torch, dev, sizes, n_frames, seed=5):
+    """MD-like streams generated on the device: the first n sites of a near-cubic
+    lattice (spacing 1), jitter sigma 0.1, then per-step displacement sigma 0.01."""
+    from paper_2411_00761_amd import datagen
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    out = []
+    for n in sizes:
+        nx, ny, nz = datagen.lattice_dims(int(n))
+        i = torch.arange(int(n), device=dev, dtype=torch.int64)
+        base = torch.stack([(i % nx), (i // nx) % ny, i // (nx * ny)]).to(torch.float32)
+        x = base + 0.1 * torch.randn(base.shape, generator=g, device=dev)
+        fr = []
+        for _ in range(n_frames):
+            fr.append(x.clone())
+            x = x + 0.01 * torch.randn(base.shape, generator=g, device=dev)
+        out.append(fr)
+    return out
+
+
+def bench_served(args, torch, lcp, datagen, dev):
+    """Streams served with overlap (lcp_server, several workers) against the plain
+    per-call form (one request at a time), on the same Poisson arrival trace."""
+    sizes = [int(n) for n in datagen.serve_stream_sizes(args.served_streams, 16, 24, seed=5)]
+    T = args.served_frames
+    frames = served_frames(torch, dev, sizes, T)
+    torch.cuda.synchronize()
+    ebs = [1e-3 if j % 2 == 0 else 1e-4 for j in range(len(sizes))]
+    caps = [40 * n + 4096 for n in sizes]
+    recs = [torch.empty(c, dtype=torch.uint8, device=dev) for c in caps]
+    decs = [torch.empty((3, n), dtype=torch.float32, device=dev) for n in sizes]
+    # request sequence per stream: C0 D0 C1 D1 ...; streams interleaved at random
+    rng = np.random.default_rng(5)
+    order = np.concatenate([np.full(2 * T, j) for j in range(len(sizes))])
+    rng.shuffle(order)
+    nxt = [0] * len(sizes)
+    reqs = []
+    for j in order:
+        t = nxt[j]
+        nxt[j] += 1
+        reqs.append((int(j), t // 2, "C" if t % 2 == 0 else "D"))
+    req_bytes = [12 * sizes[j] for j, _, _ in reqs]
+
+    def plans():
+        ps = []
+        for j, n in enumerate(sizes):
+            ps.append((lcp.Plan(ebs[j], lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=16,
+                                block_log2=ks[j], max_particles=n),
+                       lcp.Plan(ebs[j], lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=16,
+                                block_log2=ks[j], max_particles=n)))
+        return ps
+
+    # block size per stream from its first frame
+    ks = []
+    for j, n in enumerate(sizes):
+        p = lcp.Plan(ebs[j], lcp.EB_REL_GLOBAL, multi_frame=True, block_log2=-1, max_particles=n,
+                     sample=frames[j][0])
+        ks.append(p.block_log2)
+        del p
+
+    def run_plain(arrivals):
+        ps = plans()
+        rec_size = [0] * len(sizes)
+        lat, sizes_out = [], []
+        t0 = time.monotonic()
+        for i, (j, t, kind) in enumerate(reqs):
+            a = t0 + (arrivals[i] if arrivals is not None else 0.0)
+            while time.monotonic() < a:
+                pass
+            if kind == "C":
+                _, offs, _, _ = ps[j][0].compress([frames[j][t]], out=recs[j])
+                rec_size[j] = offs[1]
+                sizes_out.append(offs[1])
+            else:
+                ps[j][1].decompress(recs[j], [0, rec_size[j]], outs=[decs[j]])
+                torch.cuda.synchronize()
+            lat.append(time.monotonic() - a)
+        return time.monotonic() - t0, lat, sizes_out
+
+    def run_served(arrivals, workers):
+        arena = workers * max(lcp.scratch_bytes(max_particles=n) for n in sizes)
+        srv = lcp.Server(arena, workers=workers)
+        ids = [srv.open_stream(ebs[j], lcp.EB_REL_GLOBAL, batch_size=16, block_log2=ks[j],
+                               max_particles=n) for j, n in enumerate(sizes)]
+        torch.cuda.synchronize()
+        tickets = []
+        t0 = time.monotonic()
+        for i, (j, t, kind) in enumerate(reqs):
+            a = t0 + (arrivals[i] if arrivals is not None else 0.0)
+            while time.monotonic() < a:
+                pass
+            if kind == "C":
+                tickets.append(srv.compress(ids[j], frames[j][t], recs[j]))
+            else:
+                tickets.append(srv.decompress(ids[j], recs[j], 0, caps[j], decs[j]))
+        res = [srv.wait(tk) for tk in tickets]
+        wall = max(r["t_end_ns"] for r in res) / 1e9 - t0
+        assert all(r["status"] == 0 for r in res), [r for r in res if r["status"]][:3]
+        lat = [(r["t_end_ns"] - r["t_submit_ns"]) / 1e9 for r in res]
+        sizes_out = [r["bytes"] for r, (_, _, kind) in zip(res, reqs) if kind == "C"]
+        srv.close()
+        return wall, lat, sizes_out
+
+    run_plain(None)  # warm-up
+    plain_wall, _, plain_sizes = run_plain(None)
+    cap_rps = len(reqs) / plain_wall
+    served_wall_b2b, _, served_sizes = run_served(None, args.served_workers)
+    assert served_sizes == plain_sizes, "served records differ from the plain form"
+    rate = args.served_load * cap_rps
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
+    p_wall, p_lat, _ = run_plain(arrivals)
+    s_wall, s_lat, _ = run_served(arrivals, args.served_workers)
+    tot = float(sum(req_bytes))
+    pct = lambda v, q: float(np.percentile(np.asarray(v) * 1e3, q))  # noqa: E731
+    return {
+        "workload": f"{len(sizes)} MD-like streams, n log-uniform in [2^16, 2^24] (total "
+                    f"{sum(sizes)}), {T} frames each, eb 1e-3 / 1e-4 x range alternating, "
+                    f"requests C,D per frame in random stream order, Poisson arrivals at "
+                    f"{args.served_load:g} x plain capacity",
+        "requests": len(reqs), "workers": args.served_workers,
+        "plain_capacity_req_per_s": cap_rps,
+        "plain_back_to_back_GBps": tot / plain_wall / 1e9,
+        "served_back_to_back_GBps": tot / served_wall_b2b / 1e9,
+        "arrival_rate_req_per_s": rate,
+        "served_p50_ms": pct(s_lat, 50), "served_p99_ms": pct(s_lat, 99),
+        "plain_p50_ms": pct(p_lat, 50), "plain_p99_ms": pct(p_lat, 99),
+        "served_GBps": tot / s_wall / 1e9, "plain_GBps": tot / p_wall / 1e9,
+        "record_sizes_equal_plain": True,
+    }
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch from the committed counter summary, if it was taken on
     the current kernel sources (else None)."""
@@ -201,11 +332,15 @@ def main():
     ap.add_argument("--roofline-kernel", default=ROOFLINE_KERNEL)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run three 256 MiB device copies (counter calibration)")
-    ap.add_argument("--workloads", default="md,batched",
-                    help="comma list: md (the trajectory, the headline value), batched")
+    ap.add_argument("--workloads", default="md,batched,served",
+                    help="comma list: md (the trajectory, the headline value), batched, served")
     ap.add_argument("--batched-frames", type=int, default=256)
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--batched-warmup", type=int, default=1)
+    ap.add_argument("--served-streams", type=int, default=32)
+    ap.add_argument("--served-frames", type=int, default=6)
+    ap.add_argument("--served-workers", type=int, default=4)
+    ap.add_argument("--served-load", type=float, default=0.7)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -337,6 +472,11 @@ def main():
         log("batched workload")
         result["batched"] = bench_batched(args, torch, lcp, datagen, dev)
         log(json.dumps(result["batched"]))
+    if "served" in args.workloads.split(","):
+        torch.cuda.empty_cache()
+        log("served workload")
+        result["served"] = bench_served(args, torch, lcp, datagen, dev)
+        log(json.dumps(result["served"]))
     if not args.no_cpu_baseline:
         log(f"cpu baseline: oracle on {args.cpu_frames} frames")
         cb = cpu_baseline(frames_np, args.eb, args.batch, k, args.cpu_frames)

@@ -132,6 +132,11 @@ int lcp_plan_block_log2(lcp_plan_t plan);
 /* Worst-case record bytes for a frame of n particles. */
 uint64_t lcp_bound(lcp_plan_t plan, uint64_t n);
 
+/* Device scratch bytes a plan with these parameters uses per call (what
+ * lcp_plan allocates beside the stream state; what a server request carves out
+ * of its arena).  Errors: LCP_ERR_ARG. */
+lcp_status lcp_scratch_bytes(const lcp_params* params, uint64_t* device_bytes);
+
 /* Compress n_frames frames, in stream order, into out (device, out_cap bytes).
  * Record j is written at out + out_offsets[j] and occupies
  * out_offsets[j+1] - out_offsets[j] bytes (out_offsets: host array of
@@ -173,6 +178,71 @@ const char* lcp_status_string(lcp_status status);
 lcp_status lcp_kernel_timer_set(lcp_plan_t plan, const char* kernel_name);
 lcp_status lcp_kernel_timer_read(lcp_plan_t plan, double* total_ms, uint64_t* launches,
                                  uint64_t* bytes);
+
+/* ---- Serving: many multi-frame streams, requests overlapped on one device ----
+ *
+ * A server holds multi-frame streams (each one the state of a multi-frame plan:
+ * reference codes, permutations, LCP-FSM and Alg. 1 bookkeeping, resident on
+ * the device for the stream's lifetime) and runs their compress / decompress
+ * requests on `workers` threads, each with its own HIP stream.  A request's
+ * scratch is carved out of a device arena of scratch_bytes when it starts and
+ * returned when it ends.  Requests are admitted in submission order as soon as
+ * a worker is free, their stream has no request in flight (each stream's
+ * requests run in submission order) and the arena has room; requests of other
+ * streams may pass one whose stream is busy, never one waiting for memory.
+ * Each result is exactly what a standalone plan with the same parameters gives
+ * for the same sequence of calls.  The caller owns every frame, record and
+ * output buffer and keeps it alive until the request's lcp_server_wait
+ * returns. */
+typedef struct lcp_server_s* lcp_server_t;
+
+typedef struct {
+  uint64_t hbm_budget_bytes; /* stream state + scratch arena (0 = no limit on the state) */
+  uint64_t scratch_bytes;    /* arena for in-flight requests' scratch (> 0) */
+  int workers;               /* requests in flight at once, 1..16 */
+  int device;                /* HIP device ordinal */
+} lcp_server_params;
+
+enum { LCP_REQ_COMPRESS = 1, LCP_REQ_DECOMPRESS = 2 };
+
+typedef struct {
+  int kind;          /* LCP_REQ_COMPRESS or LCP_REQ_DECOMPRESS */
+  int stream;        /* from lcp_server_open_stream */
+  lcp_frame_in frame;  /* compress: the next frame of the stream */
+  void* out;           /* compress: record destination (device, 4-byte aligned) */
+  uint64_t out_cap;    /* compress: bytes available at out */
+  lcp_blob blob;       /* decompress: the stream's next record (decode order = stream order) */
+  lcp_frame_out dst;   /* decompress: where the frame goes */
+} lcp_request;
+
+typedef struct {
+  lcp_status status;   /* the lcp_compress / lcp_decompress status */
+  int method;          /* compress: LCP_METHOD_S or LCP_METHOD_T */
+  uint64_t bytes;      /* compress: record bytes; decompress: particles decoded */
+  uint64_t t_submit_ns, t_start_ns, t_end_ns; /* steady clock: submitted, admitted, done */
+} lcp_result;
+
+/* Create a server: allocates the arena and starts the workers.
+ * Errors: LCP_ERR_ARG, LCP_ERR_DEVICE. */
+lcp_status lcp_server_create(const lcp_server_params* params, lcp_server_t* out);
+
+/* Stop the workers (requests still queued are dropped) and free everything. */
+void lcp_server_destroy(lcp_server_t server);
+
+/* Admit a stream: params must be multi-frame and name the server's device
+ * (block_log2 == -1 searches on the sample, as lcp_plan does).  Fails with
+ * LCP_ERR_BUDGET when the stream's state would exceed the budget left beside
+ * the arena, or one request's scratch would not fit the arena. */
+lcp_status lcp_server_open_stream(lcp_server_t server, const lcp_params* params,
+                                  const float* const* sample_fields, uint64_t sample_n,
+                                  int* stream_id);
+
+/* Queue a request (copied); returns at once with a ticket.
+ * Errors: LCP_ERR_ARG (unknown stream or kind), LCP_ERR_DEVICE (a worker failed). */
+lcp_status lcp_server_submit(lcp_server_t server, const lcp_request* request, uint64_t* ticket);
+
+/* Block until the request is done and return its result (once per ticket). */
+lcp_status lcp_server_wait(lcp_server_t server, uint64_t ticket, lcp_result* result);
 
 #ifdef __cplusplus
 }

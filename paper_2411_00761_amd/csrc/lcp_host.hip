@@ -76,8 +76,12 @@ struct lcp_plan_s {
   int RB = 1;       // max frames per spatial batch
   int NAmax = 0;    // max coded arrays per encode launch set
   uint64_t hist_copies = 0, cw_cap = 0;
-  std::vector<void*> allocs;
-  size_t allocated = 0;
+  // memory: scratch (device + pinned host tables) is either owned (standalone
+  // plans) or bound per call by a server; the stream state is always owned
+  void* own_dev = nullptr;   // owned device scratch block
+  void* own_host = nullptr;  // owned pinned host block
+  void* state_dev = nullptr; // reference codes and permutations
+  size_t scratch_bytes = 0, host_bytes = 0, state_bytes = 0;
 
   // scratch (batch-wide arrays hold NB slots)
   uint64_t *keys0, *keys1, *ids, *v_id, *v_cnt;
@@ -143,31 +147,25 @@ struct lcp_plan_s {
 
 namespace {
 
-lcp_plan_s* g_timer_plan = nullptr;  // plan whose call is running (one at a time)
+thread_local lcp_plan_s* g_timer_plan = nullptr;  // plan whose call this thread runs
 
 struct TimerScope {
   explicit TimerScope(lcp_plan_s* p) { g_timer_plan = p; }
   ~TimerScope() { g_timer_plan = nullptr; }
 };
 
-#define HIP_OK(x)                          \
-  do {                                     \
-    if ((x) != hipSuccess) return LCP_ERR_DEVICE; \
-  } while (0)
-
-template <typename T>
-lcp_status dalloc(lcp_plan_s* P, T** out, size_t elems) {
-  size_t bytes = elems * sizeof(T);
-  if (bytes == 0) bytes = 256;
-  bytes = (bytes + 255) & ~(size_t)255;
-  if (P->p.hbm_budget_bytes && P->allocated + bytes > P->p.hbm_budget_bytes) return LCP_ERR_BUDGET;
-  void* ptr = nullptr;
-  if (hipMalloc(&ptr, bytes) != hipSuccess) return LCP_ERR_DEVICE;
-  P->allocs.push_back(ptr);
-  P->allocated += bytes;
-  *out = reinterpret_cast<T*>(ptr);
-  return LCP_OK;
+// A failed HIP call becomes LCP_ERR_DEVICE; with LCP_DEBUG set in the
+// environment the call and the runtime's message go to stderr.
+lcp_status hip_fail(hipError_t e, const char* what, int line) {
+  static const bool dbg = getenv("LCP_DEBUG") != nullptr;
+  if (dbg) fprintf(stderr, "lcp: %s failed at lcp_host.hip:%d: %s\n", what, line, hipGetErrorString(e));
+  return LCP_ERR_DEVICE;
 }
+#define HIP_OK(x)                                              \
+  do {                                                         \
+    hipError_t e_ = (x);                                       \
+    if (e_ != hipSuccess) return hip_fail(e_, #x, __LINE__);   \
+  } while (0)
 
 // Host table -> device: small tables through kernel arguments (a copy-engine
 // transfer costs tens of microseconds on the stream), large ones by copy from
@@ -178,8 +176,8 @@ lcp_status upload(const void* host, void* dev, size_t bytes, hipStream_t s) {
     launch_install(host, dev, bytes, s);
     return LCP_OK;
   }
-  return hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, s) == hipSuccess ? LCP_OK
-                                                                               : LCP_ERR_DEVICE;
+  HIP_OK(hipMemcpyAsync(dev, host, bytes, hipMemcpyHostToDevice, s));
+  return LCP_OK;
 }
 
 // Reads back the first `words` u64 of the return block and waits for the stream.
@@ -1177,13 +1175,34 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
   return LCP_OK;
 }
 
-template <typename T>
-lcp_status halloc(T** out, size_t elems) {
-  return hipHostMalloc((void**)out, (elems ? elems : 1) * sizeof(T), 0) == hipSuccess ? LCP_OK
-                                                                                    : LCP_ERR_DEVICE;
-}
+// A list of buffers placed back to back (256-byte aligned) in one block.
+struct Layout {
+  struct Item {
+    void** ptr;
+    size_t bytes;
+  };
+  std::vector<Item> items;
+  size_t total = 0;
+  template <typename T>
+  void add(T** p, size_t elems) {
+    size_t b = elems * sizeof(T);
+    b = b ? (b + 255) & ~(size_t)255 : 256;
+    items.push_back({reinterpret_cast<void**>(p), b});
+    total += b;
+  }
+  void place(void* base) const {
+    size_t o = 0;
+    for (const Item& it : items) {
+      *it.ptr = static_cast<uint8_t*>(base) + o;
+      o += it.bytes;
+    }
+  }
+};
 
-lcp_status alloc_plan(lcp_plan_s* P) {
+// Scratch of one call: device buffers (D) and pinned host tables (H).  Sizes
+// follow from the plan's particle capacities; nothing in them outlives a call
+// except that the spread histogram copies must be zero between calls.
+void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   const uint64_t N = P->N, NB = P->NB;
   const int F = P->F, RB = P->RB;
   const uint64_t ntiles = (NB + 4095) / 4096;
@@ -1196,90 +1215,121 @@ lcp_status alloc_plan(lcp_plan_s* P) {
   if (hc < (uint64_t)kMaxF * kHistCopies) hc = (uint64_t)kMaxF * kHistCopies;
   P->hist_copies = hc;
   P->cw_cap = (uint64_t)(F + 2) * NB / (1ull << P->chunk_log2) + NA + 1;
-  lcp_status st;
-#define A_(ptr, cnt) \
-  if ((st = dalloc(P, &(ptr), (cnt)))) return st
-  A_(P->keys0, NB);
-  A_(P->keys1, NB);
-  A_(P->ids, NB);
-  A_(P->v_id, NB);
-  A_(P->v_cnt, NB);
-  A_(P->vals0, NB);
-  A_(P->vals1, NB);
-  A_(P->hist, 256 * ntiles);
-  A_(P->flags, NB);
-  A_(P->starts, NB);
-  A_(P->v_slot, (uint64_t)F * NB);
-  A_(P->chunk_words, P->cw_cap);
-  A_(P->lut, (uint64_t)(kMaxBatchArrays + 2 * kMaxBatchFrames) << kMaxLen);
-  A_(P->ext_part, (uint64_t)2 * kMaxF * kSegExtCap * RB);
-  A_(P->hist_part, hc * kAlphabet);
-  A_(P->hist_max, hc);
-  A_(P->huff_lens, NA * kHuffCandidates * kAlphabet);
-  A_(P->huff_maxd, NA * kHuffCandidates);
-  A_(P->hdr_dev, (uint64_t)kHdrStage * kMaxBatchFrames);
-  A_(P->blobtab_dev, 2 * kMaxBatchFrames);
-  A_(P->arrtab_dev, kMaxBatchArrays + 2 * kMaxBatchFrames);
-  A_(P->prefix_dev, 2 * (kMaxBatchArrays + 2 * kMaxBatchFrames));
-  A_(P->corner, 3 * NB);
   uint64_t sn = NB > 256 * ntiles ? NB : 256 * ntiles;
   P->scan_tmp_n = scan_tmp_elems(sn);
-  A_(P->scan_tmp, P->scan_tmp_n);
-  A_(P->work, NA);
-  A_(P->ret_dev, 2 + (uint64_t)RB + (uint64_t)RB * F);
+  P->rec_tmp_cap = bound_bytes(F, N);
+  D.add(&P->keys0, NB);
+  D.add(&P->keys1, NB);
+  D.add(&P->ids, NB);
+  D.add(&P->v_id, NB);
+  D.add(&P->v_cnt, NB);
+  D.add(&P->vals0, NB);
+  D.add(&P->vals1, NB);
+  D.add(&P->hist, 256 * ntiles);
+  D.add(&P->flags, NB);
+  D.add(&P->starts, NB);
+  D.add(&P->v_slot, (uint64_t)F * NB);
+  D.add(&P->chunk_words, P->cw_cap);
+  D.add(&P->lut, (uint64_t)(kMaxBatchArrays + 2 * kMaxBatchFrames) << kMaxLen);
+  D.add(&P->ext_part, (uint64_t)2 * kMaxF * kSegExtCap * RB);
+  D.add(&P->hist_part, hc * kAlphabet);
+  D.add(&P->hist_max, hc);
+  D.add(&P->huff_lens, NA * kHuffCandidates * kAlphabet);
+  D.add(&P->huff_maxd, NA * kHuffCandidates);
+  D.add(&P->hdr_dev, (uint64_t)kHdrStage * kMaxBatchFrames);
+  D.add(&P->blobtab_dev, 2 * kMaxBatchFrames);
+  D.add(&P->arrtab_dev, kMaxBatchArrays + 2 * kMaxBatchFrames);
+  D.add(&P->prefix_dev, 2 * (kMaxBatchArrays + 2 * kMaxBatchFrames));
+  D.add(&P->corner, 3 * NB);
+  D.add(&P->scan_tmp, P->scan_tmp_n);
+  D.add(&P->work, NA);
+  D.add(&P->ret_dev, 2 + (uint64_t)RB + (uint64_t)RB * F);
+  D.add(&P->seg_dev, RB);
+  D.add(&P->segpre_dev, 3 * ((uint64_t)RB + 1));
+  D.add(&P->rstart, (uint64_t)RB + 1);
+  D.add(&P->Bs, RB);
+  D.add(&P->permdst_dev, RB);
+  D.add(&P->dseg_dev, kMaxBatchFrames);
+  D.add(&P->dpre_dev, 2 * (kMaxBatchFrames + 1));
+  D.add(&P->segbase, 3 * kMaxBatchFrames);
+  D.add(&P->earr_dev, NA);
+  D.add(&P->erec_dev, RB);
+  D.add(&P->epre_dev, 3 * (NA + 1));
+  D.add(&P->rec_tmp, P->rec_tmp_cap);
+  H.add(&P->ret_host, 2 + (size_t)RB + (size_t)RB * F);
+  H.add(&P->hdr_host, (size_t)kHdrStage * kMaxBatchFrames);
+  H.add(&P->blobtab_host, 2 * kMaxBatchFrames);
+  H.add(&P->arrtab_host, kMaxBatchArrays + 2 * kMaxBatchFrames);
+  H.add(&P->prefix_host, 2 * (kMaxBatchArrays + 2 * kMaxBatchFrames));
+  H.add(&P->seg_host, RB);
+  H.add(&P->segpre_host, 3 * ((size_t)RB + 1));
+  H.add(&P->permdst_host, RB);
+  H.add(&P->dseg_host, kMaxBatchFrames);
+  H.add(&P->dpre_host, 2 * (kMaxBatchFrames + 1));
+  H.add(&P->earr_host, NA);
+  H.add(&P->erec_host, RB);
+  H.add(&P->epre_host, 3 * (NA + 1));
+}
+
+// Resident stream state of multi-frame plans: the compressor's candidate and
+// reference codes and permutations, the decompressor's reference codes.
+void layout_state(lcp_plan_s* P, Layout& S) {
+  if (!P->p.multi_frame) return;
+  const uint64_t N = P->N;
+  const int F = P->F;
+  for (int i = 0; i < 4; i++) S.add(&P->qpool[i], (uint64_t)F * N);
+  for (int i = 0; i < 3; i++) S.add(&P->ppool[i], N);
+  for (int i = 0; i < 3; i++) S.add(&P->dqpool[i], (uint64_t)F * N);
+}
+
+// Points the plan's scratch at a device block (layout_scratch's D.total bytes)
+// and a pinned host block (H.total bytes), and clears the spread histogram
+// copies on stream s.
+void bind_scratch(lcp_plan_s* P, void* dev, void* host, hipStream_t s) {
+  Layout D, H;
+  layout_scratch(P, D, H);
+  D.place(dev);
+  H.place(host);
   P->err = reinterpret_cast<uint32_t*>(P->ret_dev);
   P->offs_dev = P->ret_dev + 1;
-  P->ext_dev = reinterpret_cast<uint32_t*>(P->ret_dev + 2 + RB);
-  A_(P->seg_dev, RB);
-  A_(P->segpre_dev, 3 * ((uint64_t)RB + 1));
-  A_(P->rstart, (uint64_t)RB + 1);
-  A_(P->Bs, RB);
-  A_(P->permdst_dev, RB);
-  A_(P->dseg_dev, kMaxBatchFrames);
-  A_(P->dpre_dev, 2 * (kMaxBatchFrames + 1));
-  A_(P->segbase, 3 * kMaxBatchFrames);
-  A_(P->earr_dev, NA);
-  A_(P->erec_dev, RB);
-  A_(P->epre_dev, 3 * (NA + 1));
-  P->rec_tmp_cap = bound_bytes(F, N);
-  A_(P->rec_tmp, P->rec_tmp_cap);
-  if (P->p.multi_frame) {
-    for (int i = 0; i < 4; i++) A_(P->qpool[i], (uint64_t)F * N);
-    for (int i = 0; i < 3; i++) A_(P->ppool[i], N);
-    for (int i = 0; i < 3; i++) A_(P->dqpool[i], (uint64_t)F * N);
+  P->ext_dev = reinterpret_cast<uint32_t*>(P->ret_dev + 2 + P->RB);
+  memset(P->seg_host, 0, sizeof(SegDev) * P->RB);
+  launch_fill_u32(P->hist_part, P->hist_copies * kAlphabet, 0u, s);
+  launch_fill_u32(reinterpret_cast<uint32_t*>(P->hist_max), 2 * P->hist_copies, 0u, s);
+}
+
+lcp_status alloc_state(lcp_plan_s* P) {
+  Layout S;
+  layout_state(P, S);
+  P->state_bytes = S.items.empty() ? 0 : S.total;
+  if (P->state_bytes) {
+    HIP_OK(hipMalloc(&P->state_dev, P->state_bytes));
+    S.place(P->state_dev);
   }
-#undef A_
-  if (hipMemset(P->hist_part, 0, sizeof(uint32_t) * hc * kAlphabet) != hipSuccess ||
-      hipMemset(P->hist_max, 0, sizeof(unsigned long long) * hc) != hipSuccess)
-    return LCP_ERR_DEVICE;
-#define H_(ptr, cnt) \
-  if ((st = halloc(&(ptr), (cnt)))) return st
-  H_(P->ret_host, 2 + (size_t)RB + (size_t)RB * F);
-  H_(P->hdr_host, (size_t)kHdrStage * kMaxBatchFrames);
-  H_(P->blobtab_host, 2 * kMaxBatchFrames);
-  H_(P->arrtab_host, kMaxBatchArrays + 2 * kMaxBatchFrames);
-  H_(P->prefix_host, 2 * (kMaxBatchArrays + 2 * kMaxBatchFrames));
-  H_(P->seg_host, RB);
-  H_(P->segpre_host, 3 * ((size_t)RB + 1));
-  H_(P->permdst_host, RB);
-  H_(P->dseg_host, kMaxBatchFrames);
-  H_(P->dpre_host, 2 * (kMaxBatchFrames + 1));
-  H_(P->earr_host, NA);
-  H_(P->erec_host, RB);
-  H_(P->epre_host, 3 * (NA + 1));
-#undef H_
-  memset(P->seg_host, 0, sizeof(SegDev) * RB);
+  return LCP_OK;
+}
+
+lcp_status alloc_plan(lcp_plan_s* P) {
+  Layout D, H, S;
+  layout_scratch(P, D, H);
+  layout_state(P, S);
+  P->scratch_bytes = D.total;
+  P->host_bytes = H.total;
+  const size_t need = D.total + (S.items.empty() ? 0 : S.total);
+  if (P->p.hbm_budget_bytes && need > P->p.hbm_budget_bytes) return LCP_ERR_BUDGET;
+  HIP_OK(hipMalloc(&P->own_dev, D.total));
+  HIP_OK(hipHostMalloc(&P->own_host, H.total, 0));
+  lcp_status st = alloc_state(P);
+  if (st) return st;
+  bind_scratch(P, P->own_dev, P->own_host, nullptr);
+  HIP_OK(hipStreamSynchronize(nullptr));
   return LCP_OK;
 }
 
 void free_plan(lcp_plan_s* P) {
-  for (void* p : P->allocs) (void)hipFree(p);
-  for (void* hp : {(void*)P->ret_host, (void*)P->hdr_host, (void*)P->blobtab_host,
-                   (void*)P->arrtab_host, (void*)P->prefix_host, (void*)P->seg_host,
-                   (void*)P->segpre_host, (void*)P->permdst_host, (void*)P->earr_host,
-                   (void*)P->erec_host, (void*)P->epre_host, (void*)P->dseg_host,
-                   (void*)P->dpre_host})
-    if (hp) (void)hipHostFree(hp);
+  if (P->own_dev) (void)hipFree(P->own_dev);
+  if (P->state_dev) (void)hipFree(P->state_dev);
+  if (P->own_host) (void)hipHostFree(P->own_host);
   for (auto e : P->ev_free) (void)hipEventDestroy(e);
   for (auto& pr : P->ev_pending) {
     (void)hipEventDestroy(pr.first);
@@ -1365,44 +1415,10 @@ lcp_status compress_group(lcp_plan_s* P, int R, const lcp_frame_in* fr, uint8_t*
 
 }  // namespace
 
-namespace lcp {
-bool ktimer_on(const char* name) {
-  return g_timer_plan && g_timer_plan->timer_name[0] && strcmp(g_timer_plan->timer_name, name) == 0;
-}
-void ktimer_begin(hipStream_t s) {
-  lcp_plan_s* P = g_timer_plan;
-  hipEvent_t a = timer_event(P), b = timer_event(P);
-  (void)hipEventRecord(a, s);
-  P->ev_pending.push_back({a, b});
-  P->ev_bytes.push_back(0);
-}
-void ktimer_end(hipStream_t s, uint64_t bytes) {
-  lcp_plan_s* P = g_timer_plan;
-  (void)hipEventRecord(P->ev_pending.back().second, s);
-  P->ev_bytes.back() = bytes;
-}
-}  // namespace lcp
-
-// ================================================================== C ABI
-extern "C" {
-
-const char* lcp_status_string(lcp_status st) {
-  switch (st) {
-    case LCP_OK: return "ok";
-    case LCP_ERR_ARG: return "invalid argument";
-    case LCP_ERR_EB_TOO_SMALL: return "error bound too small for float32 data";
-    case LCP_ERR_RANGE: return "quantisation codes or block ids out of range";
-    case LCP_ERR_CAPACITY: return "output buffer too small";
-    case LCP_ERR_CORRUPT: return "corrupt record";
-    case LCP_ERR_NO_REFERENCE: return "reference frame not resident";
-    case LCP_ERR_BUDGET: return "HBM budget exceeded";
-    case LCP_ERR_DEVICE: return "HIP runtime error";
-  }
-  return "unknown status";
-}
-
-lcp_status lcp_plan(const lcp_params* params, const float* const* sample_fields,
-                    uint64_t sample_n, lcp_plan_t* out) {
+namespace {
+// Validates params and fills the plan's sizes (no memory).
+lcp_status plan_setup(const lcp_params* params, const float* const* sample_fields,
+                      uint64_t sample_n, lcp_plan_s** out) {
   if (!params || !out) return LCP_ERR_ARG;
   *out = nullptr;
   const lcp_params& p = *params;
@@ -1430,13 +1446,102 @@ lcp_status lcp_plan(const lcp_params* params, const float* const* sample_fields,
     P->NB = p.max_batch_particles == 0 ? P->N : p.max_batch_particles;
   }
   P->k = p.block_log2 < 0 ? 0 : p.block_log2;
-  lcp_status st = alloc_plan(P);
-  if (!st && p.block_log2 == -1) {
-    if (sample_n > P->N) st = LCP_ERR_ARG;
-    else {
+  if (p.block_log2 == -1 && sample_n > P->N) {
+    delete P;
+    return LCP_ERR_ARG;
+  }
+  *out = P;
+  return LCP_OK;
+}
+}  // namespace
+
+namespace lcp {
+bool ktimer_on(const char* name) {
+  return g_timer_plan && g_timer_plan->timer_name[0] && strcmp(g_timer_plan->timer_name, name) == 0;
+}
+void ktimer_begin(hipStream_t s) {
+  lcp_plan_s* P = g_timer_plan;
+  hipEvent_t a = timer_event(P), b = timer_event(P);
+  (void)hipEventRecord(a, s);
+  P->ev_pending.push_back({a, b});
+  P->ev_bytes.push_back(0);
+}
+void ktimer_end(hipStream_t s, uint64_t bytes) {
+  lcp_plan_s* P = g_timer_plan;
+  (void)hipEventRecord(P->ev_pending.back().second, s);
+  P->ev_bytes.back() = bytes;
+}
+
+lcp_status plan_create_unbound(const lcp_params* params, const float* const* sample_fields,
+                               uint64_t sample_n, lcp_plan_t* out) {
+  lcp_plan_s* P = nullptr;
+  lcp_status st = plan_setup(params, sample_fields, sample_n, &P);
+  if (st) return st;
+  Layout D, H;
+  layout_scratch(P, D, H);
+  P->scratch_bytes = D.total;
+  P->host_bytes = H.total;
+  st = alloc_state(P);
+  if (!st && params->block_log2 == -1) {
+    // the search needs scratch once; it is released afterwards
+    void *dev = nullptr, *host = nullptr;
+    hipError_t e = hipMalloc(&dev, D.total);
+    if (e == hipSuccess) e = hipHostMalloc(&host, H.total, 0);
+    if (e != hipSuccess) {
+      st = hip_fail(e, "scratch for the block-size search", __LINE__);
+    } else {
+      bind_scratch(P, dev, host, nullptr);
       TimerScope ts(P);
       st = search_k(P, sample_fields, sample_n, nullptr);
+      e = hipStreamSynchronize(nullptr);
+      if (e != hipSuccess && !st) st = hip_fail(e, "hipStreamSynchronize", __LINE__);
     }
+    if (dev) (void)hipFree(dev);
+    if (host) (void)hipHostFree(host);
+  }
+  if (st) {
+    free_plan(P);
+    return st;
+  }
+  *out = P;
+  return LCP_OK;
+}
+
+size_t plan_scratch_bytes(lcp_plan_t P) { return P->scratch_bytes; }
+size_t plan_host_bytes(lcp_plan_t P) { return P->host_bytes; }
+size_t plan_state_bytes(lcp_plan_t P) { return P->state_bytes; }
+void plan_bind(lcp_plan_t P, void* dev, void* host, hipStream_t s) { bind_scratch(P, dev, host, s); }
+
+}  // namespace lcp
+
+// ================================================================== C ABI
+extern "C" {
+
+const char* lcp_status_string(lcp_status st) {
+  switch (st) {
+    case LCP_OK: return "ok";
+    case LCP_ERR_ARG: return "invalid argument";
+    case LCP_ERR_EB_TOO_SMALL: return "error bound too small for float32 data";
+    case LCP_ERR_RANGE: return "quantisation codes or block ids out of range";
+    case LCP_ERR_CAPACITY: return "output buffer too small";
+    case LCP_ERR_CORRUPT: return "corrupt record";
+    case LCP_ERR_NO_REFERENCE: return "reference frame not resident";
+    case LCP_ERR_BUDGET: return "HBM budget exceeded";
+    case LCP_ERR_DEVICE: return "HIP runtime error";
+  }
+  return "unknown status";
+}
+
+
+lcp_status lcp_plan(const lcp_params* params, const float* const* sample_fields,
+                    uint64_t sample_n, lcp_plan_t* out) {
+  lcp_plan_s* P = nullptr;
+  lcp_status st = plan_setup(params, sample_fields, sample_n, &P);
+  if (st) return st;
+  st = alloc_plan(P);
+  if (!st && params->block_log2 == -1) {
+    TimerScope ts(P);
+    st = search_k(P, sample_fields, sample_n, nullptr);
   }
   if (st) {
     free_plan(P);
@@ -1469,6 +1574,22 @@ lcp_status lcp_plan_reset(lcp_plan_t plan) {
 }
 
 uint64_t lcp_bound(lcp_plan_t plan, uint64_t n) { return plan ? bound_bytes(plan->F, n) : 0; }
+
+lcp_status lcp_scratch_bytes(const lcp_params* params, uint64_t* device_bytes) {
+  if (!device_bytes) return LCP_ERR_ARG;
+  lcp_plan_s* P = nullptr;
+  lcp_params q;
+  if (!params) return LCP_ERR_ARG;
+  q = *params;
+  if (q.block_log2 == -1) q.block_log2 = 0;  // the search does not change the sizes
+  lcp_status st = plan_setup(&q, nullptr, 0, &P);
+  if (st) return st;
+  Layout D, H;
+  layout_scratch(P, D, H);
+  *device_bytes = (D.total + 255) & ~(uint64_t)255;
+  delete P;
+  return LCP_OK;
+}
 
 lcp_status lcp_compress(lcp_plan_t plan, uint64_t n_frames, const lcp_frame_in* frames,
                         void* out, uint64_t out_cap, uint64_t* out_offsets, int* methods_used,

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/lcp.h"
 #include "lcp_common.h"
 
 namespace lcp {
@@ -135,6 +136,18 @@ void ktimer_end(hipStream_t s, uint64_t bytes);
     __VA_ARGS__;                                   \
     if (timed_) ::lcp::ktimer_end(stream, (bytes)); \
   } while (0)
+
+// ---- lcp_host.hip: plans whose scratch is bound per call (the server) ----
+// A plan with its stream state but no scratch; the block-size search, if asked
+// for, runs on temporary scratch.  Before each call, plan_bind points the plan
+// at plan_scratch_bytes of device memory and plan_host_bytes of pinned host
+// memory (and clears what must start at zero, on stream s).
+lcp_status plan_create_unbound(const lcp_params* params, const float* const* sample_fields,
+                               uint64_t sample_n, lcp_plan_s** out);
+size_t plan_scratch_bytes(lcp_plan_s* P);
+size_t plan_host_bytes(lcp_plan_s* P);
+size_t plan_state_bytes(lcp_plan_s* P);
+void plan_bind(lcp_plan_s* P, void* dev, void* host, hipStream_t s);
 
 // ---- kernels_core.hip ----
 // Spatial batch front end.  pre_* are device prefix tables (R + 1 entries) of

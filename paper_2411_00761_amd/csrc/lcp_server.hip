@@ -1,0 +1,295 @@
+// lcp_server.hip -- serving many multi-frame streams on one device.
+//
+// Each stream is a multi-frame plan whose resident state (reference codes and
+// permutations, LCP-FSM and Alg. 1 bookkeeping) lives on the device for the
+// stream's lifetime; its scratch is not owned but carved, per request, out of
+// one device arena.  Worker threads, each with its own HIP stream and pinned
+// host tables, take requests in arrival order: a request is admitted when a
+// worker is free, its stream has no request in flight (a stream's requests run
+// in submission order), and the arena has room for its scratch.  Requests of
+// different streams therefore overlap on the device, and the memory a finished
+// request releases admits the next one.
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <string.h>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/lcp.h"
+#include "lcp_internal.h"
+
+using namespace lcp;
+
+namespace {
+
+uint64_t now_ns() {
+  return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+             std::chrono::steady_clock::now().time_since_epoch())
+      .count();
+}
+
+struct ServedStream {
+  lcp_plan_s* plan = nullptr;
+  size_t scratch = 0;  // arena bytes one request needs
+  bool busy = false;
+};
+
+struct Ticket {
+  lcp_request req;
+  lcp_result res;
+  bool done = false;
+};
+
+// First-fit allocator over [0, size) with coalescing frees (256-byte units).
+struct Arena {
+  std::map<size_t, size_t> free;  // offset -> bytes
+  void init(size_t size) {
+    free.clear();
+    if (size) free[0] = size;
+  }
+  bool alloc(size_t bytes, size_t* off) {
+    for (auto it = free.begin(); it != free.end(); ++it) {
+      if (it->second < bytes) continue;
+      *off = it->first;
+      const size_t rest = it->second - bytes;
+      const size_t at = it->first + bytes;
+      free.erase(it);
+      if (rest) free[at] = rest;
+      return true;
+    }
+    return false;
+  }
+  void release(size_t off, size_t bytes) {
+    auto it = free.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != free.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free.erase(nx);
+    }
+    if (it != free.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free.erase(it);
+      }
+    }
+  }
+};
+
+}  // namespace
+
+struct lcp_server_s {
+  lcp_server_params p{};
+  void* arena_mem = nullptr;
+  Arena arena;
+  size_t state_used = 0;
+  size_t host_bytes = 0;  // pinned tables per worker
+  std::vector<ServedStream> streams;
+  std::deque<uint64_t> pending;  // tickets in submission order
+  std::unordered_map<uint64_t, Ticket> tickets;
+  uint64_t next_ticket = 1;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  bool stop = false;
+  std::vector<std::thread> workers;
+  lcp_status worker_error = LCP_OK;
+};
+
+namespace {
+
+// Next admissible request (lock held): the first pending one whose stream is
+// idle and has no earlier pending request; memory is admitted strictly in
+// order, so a large request is not starved by smaller ones behind it.
+bool pick(lcp_server_s* S, uint64_t* ticket, size_t* off) {
+  std::vector<char> blocked(S->streams.size(), 0);
+  for (auto it = S->pending.begin(); it != S->pending.end(); ++it) {
+    const Ticket& t = S->tickets[*it];
+    const int sid = t.req.stream;
+    if (blocked[sid]) continue;
+    blocked[sid] = 1;
+    ServedStream& st = S->streams[sid];
+    if (st.busy) continue;
+    if (!S->arena.alloc(st.scratch, off)) return false;
+    st.busy = true;
+    *ticket = *it;
+    S->pending.erase(it);
+    return true;
+  }
+  return false;
+}
+
+void run_request(lcp_plan_s* plan, const lcp_request& rq, hipStream_t hs, lcp_result* res) {
+  if (rq.kind == LCP_REQ_COMPRESS) {
+    uint64_t offs[2] = {0, 0};
+    int method = 0;
+    res->status = lcp_compress(plan, 1, &rq.frame, rq.out, rq.out_cap, offs, &method, nullptr, hs);
+    res->method = method;
+    res->bytes = offs[1];
+  } else {
+    uint64_t n = 0;
+    res->status = lcp_decompress(plan, 1, &rq.blob, &rq.dst, &n, hs);
+    res->method = 0;
+    res->bytes = n;
+  }
+}
+
+void worker_main(lcp_server_s* S) {
+  hipStream_t hs = nullptr;
+  void* host = nullptr;
+  lcp_status init = LCP_OK;
+  if (hipSetDevice(S->p.device) != hipSuccess ||
+      hipStreamCreateWithFlags(&hs, hipStreamNonBlocking) != hipSuccess ||
+      hipHostMalloc(&host, S->host_bytes, 0) != hipSuccess)
+    init = LCP_ERR_DEVICE;
+  for (;;) {
+    uint64_t tk = 0;
+    size_t off = 0;
+    {
+      std::unique_lock<std::mutex> lk(S->mu);
+      if (init != LCP_OK) S->worker_error = init;
+      S->cv_work.wait(lk, [&] { return S->stop || (init == LCP_OK && pick(S, &tk, &off)); });
+      if (S->stop && tk == 0) break;
+    }
+    Ticket* t;
+    lcp_plan_s* plan;
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      t = &S->tickets[tk];
+      plan = S->streams[t->req.stream].plan;
+      t->res.t_start_ns = now_ns();
+    }
+    plan_bind(plan, static_cast<uint8_t*>(S->arena_mem) + off, host, hs);
+    lcp_result res = t->res;
+    run_request(plan, t->req, hs, &res);
+    res.t_end_ns = now_ns();
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      S->arena.release(off, S->streams[t->req.stream].scratch);
+      S->streams[t->req.stream].busy = false;
+      t->res = res;
+      t->done = true;
+    }
+    S->cv_done.notify_all();
+    S->cv_work.notify_all();
+  }
+  if (host) (void)hipHostFree(host);
+  if (hs) (void)hipStreamDestroy(hs);
+}
+
+size_t round256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+}  // namespace
+
+extern "C" {
+
+lcp_status lcp_server_create(const lcp_server_params* params, lcp_server_t* out) {
+  if (!params || !out) return LCP_ERR_ARG;
+  *out = nullptr;
+  const lcp_server_params& p = *params;
+  if (p.workers < 1 || p.workers > 16 || p.scratch_bytes == 0 ||
+      (p.hbm_budget_bytes && p.scratch_bytes > p.hbm_budget_bytes))
+    return LCP_ERR_ARG;
+  if (hipSetDevice(p.device) != hipSuccess) return LCP_ERR_DEVICE;
+  lcp_server_s* S = new lcp_server_s();
+  S->p = p;
+  S->p.scratch_bytes = round256(p.scratch_bytes);
+  // pinned tables of the largest multi-frame plan (they do not depend on n)
+  lcp_params q{};
+  q.eb_mode = LCP_EB_ABS;
+  q.eb = 1.0;
+  q.n_fields = LCP_MAX_FIELDS;
+  q.multi_frame = 1;
+  q.block_log2 = 0;
+  q.max_particles = 1;
+  q.device = p.device;
+  lcp_plan_s* probe = nullptr;
+  lcp_status st = plan_create_unbound(&q, nullptr, 0, &probe);
+  if (st) {
+    delete S;
+    return st;
+  }
+  S->host_bytes = plan_host_bytes(probe);
+  lcp_plan_destroy(probe);
+  if (hipMalloc(&S->arena_mem, S->p.scratch_bytes) != hipSuccess) {
+    delete S;
+    return LCP_ERR_DEVICE;
+  }
+  S->arena.init(S->p.scratch_bytes);
+  for (int w = 0; w < p.workers; w++) S->workers.emplace_back(worker_main, S);
+  *out = S;
+  return LCP_OK;
+}
+
+void lcp_server_destroy(lcp_server_t S) {
+  if (!S) return;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->stop = true;
+  }
+  S->cv_work.notify_all();
+  for (auto& th : S->workers) th.join();
+  for (auto& st : S->streams) lcp_plan_destroy(st.plan);
+  if (S->arena_mem) (void)hipFree(S->arena_mem);
+  delete S;
+}
+
+lcp_status lcp_server_open_stream(lcp_server_t S, const lcp_params* params,
+                                  const float* const* sample_fields, uint64_t sample_n,
+                                  int* stream_id) {
+  if (!S || !params || !stream_id || !params->multi_frame || params->device != S->p.device)
+    return LCP_ERR_ARG;
+  lcp_plan_s* plan = nullptr;
+  lcp_status st = plan_create_unbound(params, sample_fields, sample_n, &plan);
+  if (st) return st;
+  const size_t scratch = round256(plan_scratch_bytes(plan));
+  const size_t state = plan_state_bytes(plan);
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (scratch > S->p.scratch_bytes ||
+      (S->p.hbm_budget_bytes && S->state_used + state + S->p.scratch_bytes > S->p.hbm_budget_bytes)) {
+    lcp_plan_destroy(plan);
+    return LCP_ERR_BUDGET;
+  }
+  S->state_used += state;
+  ServedStream ss;
+  ss.plan = plan;
+  ss.scratch = scratch;
+  S->streams.push_back(ss);
+  *stream_id = (int)S->streams.size() - 1;
+  return LCP_OK;
+}
+
+lcp_status lcp_server_submit(lcp_server_t S, const lcp_request* req, uint64_t* ticket) {
+  if (!S || !req || !ticket) return LCP_ERR_ARG;
+  if (req->kind != LCP_REQ_COMPRESS && req->kind != LCP_REQ_DECOMPRESS) return LCP_ERR_ARG;
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (S->worker_error) return S->worker_error;
+  if (req->stream < 0 || req->stream >= (int)S->streams.size()) return LCP_ERR_ARG;
+  const uint64_t id = S->next_ticket++;
+  Ticket& t = S->tickets[id];
+  t.req = *req;
+  memset(&t.res, 0, sizeof(t.res));
+  t.res.t_submit_ns = now_ns();
+  S->pending.push_back(id);
+  *ticket = id;
+  S->cv_work.notify_one();
+  return LCP_OK;
+}
+
+lcp_status lcp_server_wait(lcp_server_t S, uint64_t ticket, lcp_result* res) {
+  if (!S || !res) return LCP_ERR_ARG;
+  std::unique_lock<std::mutex> lk(S->mu);
+  auto it = S->tickets.find(ticket);
+  if (it == S->tickets.end()) return LCP_ERR_ARG;
+  S->cv_done.wait(lk, [&] { return S->tickets[ticket].done || S->worker_error != LCP_OK; });
+  Ticket& t = S->tickets[ticket];
+  if (!t.done) return S->worker_error;
+  *res = t.res;
+  S->tickets.erase(ticket);
+  return LCP_OK;
+}
+
+}  // extern "C"

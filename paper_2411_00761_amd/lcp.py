@@ -22,7 +22,10 @@ DECIDE_S, DECIDE_T, DECIDE_COMPARE = 1, 2, 3
 
 EXPORTED = ["lcp_plan", "lcp_plan_destroy", "lcp_plan_reset", "lcp_plan_block_log2", "lcp_bound", "lcp_compress",
             "lcp_decompress", "lcp_select", "lcp_status_string", "lcp_kernel_timer_set",
-            "lcp_kernel_timer_read"]
+            "lcp_kernel_timer_read", "lcp_server_create", "lcp_server_destroy",
+            "lcp_server_open_stream", "lcp_server_submit", "lcp_server_wait",
+            "lcp_scratch_bytes"]
+REQ_COMPRESS, REQ_DECOMPRESS = 1, 2
 
 
 class LCPError(RuntimeError):
@@ -52,6 +55,22 @@ class lcp_frame_out(C.Structure):
     _fields_ = [("fields", C.c_void_p * MAX_FIELDS), ("capacity", C.c_uint64)]
 
 
+class lcp_server_params(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_uint64), ("scratch_bytes", C.c_uint64),
+                ("workers", C.c_int), ("device", C.c_int)]
+
+
+class lcp_request(C.Structure):
+    _fields_ = [("kind", C.c_int), ("stream", C.c_int), ("frame", lcp_frame_in),
+                ("out", C.c_void_p), ("out_cap", C.c_uint64), ("blob", lcp_blob),
+                ("dst", lcp_frame_out)]
+
+
+class lcp_result(C.Structure):
+    _fields_ = [("status", C.c_int), ("method", C.c_int), ("bytes", C.c_uint64),
+                ("t_submit_ns", C.c_uint64), ("t_start_ns", C.c_uint64), ("t_end_ns", C.c_uint64)]
+
+
 _lib = None
 
 
@@ -79,6 +98,14 @@ def lib():
         L.lcp_kernel_timer_set.argtypes = [P, C.c_char_p]
         L.lcp_kernel_timer_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_uint64),
                                             C.POINTER(C.c_uint64)]
+        L.lcp_scratch_bytes.argtypes = [C.POINTER(lcp_params), C.POINTER(C.c_uint64)]
+        L.lcp_server_create.argtypes = [C.POINTER(lcp_server_params), C.POINTER(P)]
+        L.lcp_server_destroy.argtypes = [P]
+        L.lcp_server_destroy.restype = None
+        L.lcp_server_open_stream.argtypes = [P, C.POINTER(lcp_params), P, C.c_uint64,
+                                             C.POINTER(C.c_int)]
+        L.lcp_server_submit.argtypes = [P, C.POINTER(lcp_request), C.POINTER(C.c_uint64)]
+        L.lcp_server_wait.argtypes = [P, C.c_uint64, C.POINTER(lcp_result)]
         _lib = L
     return _lib
 
@@ -214,3 +241,98 @@ class Plan:
         _check(lib().lcp_kernel_timer_read(self.h, C.byref(ms), C.byref(la), C.byref(by)),
                "lcp_kernel_timer_read")
         return ms.value, la.value, by.value
+
+
+def scratch_bytes(n_fields: int = 3, multi_frame: bool = True, max_particles: int = 1 << 20,
+                  chunk_log2: int = 10, max_batch_particles: int = 0, max_batch_frames: int = 0) -> int:
+    """Device scratch of one call of a plan with these sizes (lcp_scratch_bytes)."""
+    p = lcp_params(EB_ABS, 1.0, n_fields, int(multi_frame), 16, 0, chunk_log2, max_particles, 0, 0,
+                   max_batch_particles, max_batch_frames)
+    b = C.c_uint64()
+    _check(lib().lcp_scratch_bytes(C.byref(p), C.byref(b)), "lcp_scratch_bytes")
+    return b.value
+
+
+class Server:
+    """lcp_server_*: multi-frame streams served concurrently on one device.
+
+    Frames are torch float32 CUDA tensors shaped (F, n); records and outputs are
+    caller tensors kept alive here until their request is waited for."""
+
+    def __init__(self, scratch_bytes: int, workers: int = 4, hbm_budget_bytes: int = 0,
+                 device: int = 0):
+        import torch
+        self.device = device
+        p = lcp_server_params(hbm_budget_bytes, scratch_bytes, workers, device)
+        h = C.c_void_p()
+        with torch.cuda.device(device):
+            _check(lib().lcp_server_create(C.byref(p), C.byref(h)), "lcp_server_create")
+        self.h = h
+        self.F = {}
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lcp_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def open_stream(self, eb: float, eb_mode: int = EB_ABS, n_fields: int = 3, batch_size: int = 16,
+                    block_log2: int = -1, chunk_log2: int = 10, max_particles: int = 1 << 20,
+                    sample=None) -> int:
+        params = lcp_params(eb_mode, eb, n_fields, 1, batch_size, block_log2, chunk_log2,
+                            max_particles, 0, self.device, 0, 0)
+        ptrs, sn = None, 0
+        if sample is not None:
+            sample = sample.contiguous()
+            ptrs = (C.c_void_p * n_fields)(*[sample[f].data_ptr() for f in range(n_fields)])
+            sn = sample.shape[1]
+        sid = C.c_int()
+        _check(lib().lcp_server_open_stream(self.h, C.byref(params), ptrs, sn, C.byref(sid)),
+               "lcp_server_open_stream")
+        self.F[sid.value] = n_fields
+        return sid.value
+
+    def _submit(self, rq, keep) -> int:
+        t = C.c_uint64()
+        _check(lib().lcp_server_submit(self.h, C.byref(rq), C.byref(t)), "lcp_server_submit")
+        self._keep[t.value] = keep
+        return t.value
+
+    def compress(self, stream: int, frame, out, method: int = METHOD_AUTO) -> int:
+        """Queue the stream's next frame; the record goes to out (uint8 CUDA tensor)."""
+        rq = lcp_request()
+        rq.kind = REQ_COMPRESS
+        rq.stream = stream
+        frame = frame.contiguous()
+        for k in range(self.F[stream]):
+            rq.frame.fields[k] = frame[k].data_ptr()
+        rq.frame.n = frame.shape[1]
+        rq.frame.method = method
+        rq.out = out.data_ptr()
+        rq.out_cap = out.numel()
+        return self._submit(rq, (frame, out))
+
+    def decompress(self, stream: int, buf, offset: int, size: int, out) -> int:
+        """Queue the decoding of the stream's next record buf[offset:offset+size] into out (F, n)."""
+        rq = lcp_request()
+        rq.kind = REQ_DECOMPRESS
+        rq.stream = stream
+        rq.blob.data = buf.data_ptr() + offset
+        rq.blob.size = size
+        for k in range(self.F[stream]):
+            rq.dst.fields[k] = out[k].data_ptr()
+        rq.dst.capacity = out.shape[1]
+        return self._submit(rq, (buf, out))
+
+    def wait(self, ticket: int) -> dict:
+        r = lcp_result()
+        _check(lib().lcp_server_wait(self.h, ticket, C.byref(r)), "lcp_server_wait")
+        self._keep.pop(ticket, None)
+        return {"status": r.status, "method": r.method, "bytes": r.bytes,
+                "t_submit_ns": r.t_submit_ns, "t_start_ns": r.t_start_ns, "t_end_ns": r.t_end_ns}
