@@ -123,35 +123,6 @@ __global__ __launch_bounds__(kThreads) void k_hist(const EncArr* E, const uint32
   if (threadIdx.x == 0 && bm) atomicMax(&part_max[copy], bm);
 }
 
-// Sums the spread copies per bin and clears them for the next use.
-__global__ __launch_bounds__(kThreads) void k_hist_reduce(const EncArr* E, uint32_t* part,
-                                                          unsigned long long* part_max,
-                                                          ArrWork* W) {
-  const int a = blockIdx.y;
-  const EncArr& e = E[a];
-  ArrWork& w = W[a];
-  uint32_t* src = part + (uint64_t)e.copy0 * kAlphabet;
-  const int j = blockIdx.x * kThreads + threadIdx.x;
-  if (j < kAlphabet) {
-    uint32_t t = 0;
-    for (uint32_t c = 0; c < e.copies; c++) {
-      t += src[(uint64_t)c * kAlphabet + j];
-      src[(uint64_t)c * kAlphabet + j] = 0;
-    }
-    w.hist[j] = t;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    unsigned long long m = 0;
-    for (uint32_t c = 0; c < e.copies; c++) {
-      unsigned long long v = part_max[e.copy0 + c];
-      m = v > m ? v : m;
-      part_max[e.copy0 + c] = 0;
-    }
-    w.maxv = m;
-    w.n = (uint32_t)arr_len(e.in);
-  }
-}
-
 // ------------------------------------------------------------------ Huffman build
 // LDS layout of the 64 KB buffer (U <= 4148 used symbols):
 //   [0, 16592)      leaf weights u32 [U]        -> later depths u16 [2U-1]
@@ -179,48 +150,31 @@ __device__ inline uint32_t block_max_u32(uint32_t v, uint32_t* misc) {
   return t;
 }
 
-// Code lengths for one array and one halving count h (workgroup (a, h)): counts
-// c -> ceil(c / 2) applied h times, then one Huffman build.  The oracle's loop
-// (halve until the longest code fits) is the smallest h whose build fits; all
-// candidate h run side by side and k_huff_codes picks that smallest one.
-constexpr int kHalvings = 32;  // counts < 2^31: after 31 halvings every count is 1
+// Code lengths from this thread's counts c[j] (symbols t + kHT * j): one
+// Huffman build.  Leaves are the used symbols sorted by (count, symbol)
+// (bitonic sort), merged by one thread with two queues (leaves in order,
+// internal nodes FIFO, the lighter head first and the leaf on a tie), depths
+// by pointer jumping.  The lengths go to lens_g (global) and to LDS at
+// kOffLens; returns the longest code (block-uniform).
+constexpr int kPer = (kAlphabet + kHT - 1) / kHT;  // 5 symbols per thread
 
-__global__ __launch_bounds__(kHT) void k_huff_lengths(const ArrWork* W, uint8_t* lens_all,
-                                                      uint32_t* maxd_all, int h0, int gate) {
-  __shared__ uint64_t sm64[8192];
-  uint8_t* smb = reinterpret_cast<uint8_t*>(sm64);
+__device__ uint32_t huff_build(const uint32_t* c, uint8_t* smb, uint8_t* lens_g) {
+  uint64_t* sm64 = reinterpret_cast<uint64_t*>(smb);
   uint32_t* leafw = reinterpret_cast<uint32_t*>(smb);
   uint16_t* dist = reinterpret_cast<uint16_t*>(smb);
   uint16_t* leafsym = reinterpret_cast<uint16_t*>(smb + kOffLeafSym);
   uint32_t* intw = reinterpret_cast<uint32_t*>(smb + kOffInt);
   uint16_t* anc = reinterpret_cast<uint16_t*>(smb + kOffInt);
   uint16_t* parent = reinterpret_cast<uint16_t*>(smb + kOffParent);
+  uint8_t* lens_l = smb + kOffLens;
   uint32_t* misc = reinterpret_cast<uint32_t*>(smb + kOffMisc);
-
-  const int a = blockIdx.x, halvings = blockIdx.y + h0;
-  // gate: halvings are only needed when the plain build is too deep
-  if (gate && maxd_all[(uint64_t)a * kHalvings] <= (uint32_t)kMaxLen) return;
-  const ArrWork& w = W[a];
   const int t = threadIdx.x;
-  uint8_t* lens = lens_all + ((uint64_t)a * kHalvings + halvings) * kAlphabet;
-  uint32_t* maxd = maxd_all + (uint64_t)a * kHalvings + halvings;
-  if (w.n == 0) {
-    if (t == 0) *maxd = 0;
-    return;
-  }
-  constexpr int kPer = (kAlphabet + kHT - 1) / kHT;  // 5 symbols per thread
-  // ---- leaves: used symbols with their halved counts
-  uint32_t c[kPer];
+  // ---- leaves: used symbols with their counts
   uint32_t mine = 0;
 #pragma unroll
-  for (int j = 0; j < kPer; j++) {
-    int s = t + kHT * j;
-    uint32_t cc = s < kAlphabet ? w.hist[s] : 0u;
-    for (int h = 0; h < halvings && cc > 1; h++) cc = (cc + 1u) >> 1;
-    c[j] = cc;
-    mine += cc ? 1u : 0u;
-  }
+  for (int j = 0; j < kPer; j++) mine += c[j] ? 1u : 0u;
   uint32_t incl = wave_incl_scan(mine);
+  __syncthreads();
   if (lane_id() == kWave - 1) misc[wave_id()] = incl;
   __syncthreads();
   uint32_t before = 0, U = 0;
@@ -236,12 +190,17 @@ __global__ __launch_bounds__(kHT) void k_huff_lengths(const ArrWork* W, uint8_t*
     int s = t + kHT * j;
     if (c[j]) sm64[pos++] = ((uint64_t)c[j] << 13) | (uint64_t)s;
   }
+  __syncthreads();
   if (U == 1) {
-    __syncthreads();
     uint32_t only = (uint32_t)(sm64[0] & 0x1FFFu);
-    for (int s = t; s < kAlphabet; s += kHT) lens[s] = (uint32_t)s == only ? 1 : 0;
-    if (t == 0) *maxd = 1;
-    return;
+    __syncthreads();
+    for (int s = t; s < kAlphabet; s += kHT) {
+      const uint8_t l = (uint32_t)s == only ? 1 : 0;
+      lens_g[s] = l;
+      lens_l[s] = l;
+    }
+    __syncthreads();
+    return 1;
   }
   uint32_t P = 2;
   while (P < U) P <<= 1;
@@ -280,9 +239,8 @@ __global__ __launch_bounds__(kHT) void k_huff_lengths(const ArrWork* W, uint8_t*
     }
   }
   __syncthreads();
-  // ---- two-queue merge: leaves in sorted order, internal nodes FIFO in
-  // creation order; the lighter head is taken, the leaf on a tie.  The four
-  // candidates of a step are loaded together; a missing one reads as +inf.
+  // ---- two-queue merge; the four candidates of a step are loaded together, a
+  // missing one reads as +inf
   if (t == 0) {
     constexpr uint32_t kInf = 0xFFFFFFFFu;
     uint32_t li = 0, ii = 0, nxt = 0;
@@ -360,7 +318,10 @@ __global__ __launch_bounds__(kHT) void k_huff_lengths(const ArrWork* W, uint8_t*
     }
     __syncthreads();
   }
-  for (int s = t; s < kAlphabet; s += kHT) lens[s] = 0;
+  for (int s = t; s < kAlphabet; s += kHT) {
+    lens_g[s] = 0;
+    lens_l[s] = 0;
+  }
   __syncthreads();
   uint32_t md = 0;
 #pragma unroll
@@ -368,44 +329,24 @@ __global__ __launch_bounds__(kHT) void k_huff_lengths(const ArrWork* W, uint8_t*
     uint32_t i = t + kHT * j;
     if (i < U) {
       md = max(md, (uint32_t)dist[i]);
-      lens[leafsym[i]] = (uint8_t)(dist[i] > 255 ? 255 : dist[i]);
+      const uint8_t l = (uint8_t)(dist[i] > 255 ? 255 : dist[i]);
+      lens_g[leafsym[i]] = l;
+      lens_l[leafsym[i]] = l;
     }
   }
   md = block_max_u32(md, misc);
-  if (t == 0) *maxd = md;
+  return md;
 }
 
-// Picks the fewest halvings whose longest code fits, then canonical codes:
-// shorter first, ties by symbol (RFC 1951 order), and the table of used symbols.
-__global__ __launch_bounds__(kHT) void k_huff_codes(ArrWork* W, const uint8_t* lens_all,
-                                                    const uint32_t* maxd_all) {
-  __shared__ uint8_t lens[kAlphabet];
-  __shared__ uint32_t wcnt[kHT / kWave * 16];
-  __shared__ uint32_t misc[64];
-  const int a = blockIdx.x;
-  ArrWork& w = W[a];
+// Canonical codes from code lengths in LDS: shorter first, ties by symbol
+// (RFC 1951 order), and the table of used symbols.  wcnt: kHT / kWave * 16
+// u32 and misc: 64 u32 of LDS scratch.
+__device__ void huff_codes(ArrWork& w, const uint8_t* lens, uint32_t* wcnt, uint32_t* misc) {
   const int t = threadIdx.x;
-  if (w.n == 0) {
-    for (int s = t; s < kAlphabet; s += kHT) w.lc[s] = 0;
-    if (t == 0) {
-      w.U = 0;
-      w.L = 0;
-    }
-    return;
-  }
-  // the first (fewest halvings) build that fits; 31 halvings always fit, and
-  // candidates past the first fit may not have been built
-  int hsel = kHalvings - 1;
-  for (int h = 0; h < kHalvings - 1; h++)
-    if (maxd_all[(uint64_t)a * kHalvings + h] <= (uint32_t)kMaxLen) {
-      hsel = h;
-      break;
-    }
-  const uint8_t* src = lens_all + ((uint64_t)a * kHalvings + hsel) * kAlphabet;
-  for (int s = t; s < kAlphabet; s += kHT) lens[s] = src[s];
   uint32_t* blc = misc;        // [16] code-length counts
   uint32_t* first = misc + 16; // [16] first code per length
   uint32_t* run = misc + 32;   // [16] codes given so far / table size
+  __syncthreads();
   if (t < 48) misc[t] = 0;
   __syncthreads();
   uint32_t lmax = 0;
@@ -464,6 +405,121 @@ __global__ __launch_bounds__(kHT) void k_huff_codes(ArrWork* W, const uint8_t* l
     w.U = run[0];
     w.L = lmax;
   }
+}
+
+__device__ inline void empty_codes(ArrWork& w) {
+  for (int s = threadIdx.x; s < kAlphabet; s += kHT) w.lc[s] = 0;
+  if (threadIdx.x == 0) {
+    w.U = 0;
+    w.L = 0;
+  }
+}
+
+// One array per workgroup: sums its spread histogram copies (only the bins up
+// to the largest value's symbol can be non-zero) and clears them, builds the
+// code with no halving and, when its longest code fits kMaxLen bits, the
+// canonical codes.  maxd_all[a][0] tells the fallback launches whether they
+// are needed.
+constexpr int kHalvings = 32;  // counts < 2^31: after 31 halvings every count is 1
+
+__global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* part,
+                                                    unsigned long long* part_max, ArrWork* W,
+                                                    uint8_t* lens_all, uint32_t* maxd_all) {
+  __shared__ uint64_t sm64[8192];
+  __shared__ unsigned long long smx[kHT / kWave];
+  uint8_t* smb = reinterpret_cast<uint8_t*>(sm64);
+  const int a = blockIdx.x, t = threadIdx.x;
+  const EncArr& e = E[a];
+  ArrWork& w = W[a];
+  // largest value over the copies (and clear them)
+  unsigned long long mx = 0;
+  for (uint32_t c = t; c < e.copies; c += kHT) {
+    const unsigned long long v = part_max[e.copy0 + c];
+    mx = v > mx ? v : mx;
+    part_max[e.copy0 + c] = 0;
+  }
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) {
+    const unsigned long long o = shfl_xor_u64(mx, d);
+    mx = o > mx ? o : mx;
+  }
+  if (lane_id() == 0) smx[wave_id()] = mx;
+  __syncthreads();
+  mx = 0;
+  for (int j = 0; j < kHT / kWave; j++) mx = smx[j] > mx ? smx[j] : mx;
+  const uint64_t n = arr_len(e.in);
+  const int top = n ? sym_bound(mx) : -1;
+  uint32_t cnt[kPer];
+  uint32_t* src = part + (uint64_t)e.copy0 * kAlphabet;
+#pragma unroll
+  for (int j = 0; j < kPer; j++) {
+    const int s = t + kHT * j;
+    uint32_t v = 0;
+    if (s <= top)
+      for (uint32_t c = 0; c < e.copies; c++) {
+        v += src[(uint64_t)c * kAlphabet + s];
+        src[(uint64_t)c * kAlphabet + s] = 0;
+      }
+    cnt[j] = v;
+    if (s < kAlphabet) w.hist[s] = v;
+  }
+  if (t == 0) {
+    w.maxv = mx;
+    w.n = (uint32_t)n;
+  }
+  uint32_t* maxd = maxd_all + (uint64_t)a * kHalvings;
+  if (n == 0) {
+    empty_codes(w);
+    if (t == 0) maxd[0] = 0;
+    return;
+  }
+  const uint32_t md = huff_build(cnt, smb, lens_all + (uint64_t)a * kHalvings * kAlphabet);
+  if (t == 0) maxd[0] = md;
+  if (md > (uint32_t)kMaxLen) return;
+  huff_codes(w, smb + kOffLens, reinterpret_cast<uint32_t*>(smb), reinterpret_cast<uint32_t*>(smb + kOffMisc));
+}
+
+// Fallback for arrays whose plain build is too deep (the oracle's loop halves
+// the counts, c -> ceil(c / 2), until the longest code fits): workgroup (a, h)
+// builds with h = blockIdx.y + 1 halvings, all candidates side by side.
+__global__ __launch_bounds__(kHT) void k_huff_lengths(const ArrWork* W, uint8_t* lens_all,
+                                                      uint32_t* maxd_all) {
+  __shared__ uint64_t sm64[8192];
+  const int a = blockIdx.x, halvings = blockIdx.y + 1;
+  if (maxd_all[(uint64_t)a * kHalvings] <= (uint32_t)kMaxLen) return;
+  const ArrWork& w = W[a];
+  const int t = threadIdx.x;
+  uint32_t c[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; j++) {
+    int s = t + kHT * j;
+    uint32_t cc = s < kAlphabet ? w.hist[s] : 0u;
+    for (int h = 0; h < halvings && cc > 1; h++) cc = (cc + 1u) >> 1;
+    c[j] = cc;
+  }
+  const uint32_t md = huff_build(c, reinterpret_cast<uint8_t*>(sm64),
+                                 lens_all + ((uint64_t)a * kHalvings + halvings) * kAlphabet);
+  if (t == 0) maxd_all[(uint64_t)a * kHalvings + halvings] = md;
+}
+
+// Fallback codes: the fewest halvings whose longest code fits (31 always fit).
+__global__ __launch_bounds__(kHT) void k_huff_codes(ArrWork* W, const uint8_t* lens_all,
+                                                    const uint32_t* maxd_all) {
+  __shared__ uint8_t lens[kAlphabet];
+  __shared__ uint32_t wcnt[kHT / kWave * 16];
+  __shared__ uint32_t misc[64];
+  const int a = blockIdx.x;
+  if (maxd_all[(uint64_t)a * kHalvings] <= (uint32_t)kMaxLen) return;
+  ArrWork& w = W[a];
+  int hsel = kHalvings - 1;
+  for (int h = 1; h < kHalvings - 1; h++)
+    if (maxd_all[(uint64_t)a * kHalvings + h] <= (uint32_t)kMaxLen) {
+      hsel = h;
+      break;
+    }
+  const uint8_t* src = lens_all + ((uint64_t)a * kHalvings + hsel) * kAlphabet;
+  for (int s = threadIdx.x; s < kAlphabet; s += kHT) lens[s] = src[s];
+  huff_codes(w, lens, wcnt, misc);
 }
 
 // ------------------------------------------------------------------ chunk sizes
@@ -1142,16 +1198,10 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, uint32_t* 
   if (!hist_done)
     LCP_TIMED("hist", L.values * 4ull, s,
               k_hist<<<L.hist_blocks, kThreads, 0, s>>>(L.arrs, pre_hist, NA, hist_part, hist_max));
-  k_hist_reduce<<<dim3((kAlphabet + kThreads - 1) / kThreads, NA), kThreads, 0, s>>>(
-      L.arrs, hist_part, hist_max, work);
-  // Few arrays: all halving counts side by side.  Many: the plain build first,
-  // then the halvings only for the arrays whose plain build is too deep.
-  if (NA <= 16) {
-    k_huff_lengths<<<dim3(NA, kHalvings), kHT, 0, s>>>(work, huff_lens, huff_maxd, 0, 0);
-  } else {
-    k_huff_lengths<<<dim3(NA, 1), kHT, 0, s>>>(work, huff_lens, huff_maxd, 0, 0);
-    k_huff_lengths<<<dim3(NA, kHalvings - 1), kHT, 0, s>>>(work, huff_lens, huff_maxd, 1, 1);
-  }
+  // the plain build (and its codes) per array; the halving candidates and their
+  // codes only run for arrays whose plain build is too deep
+  k_huff_build<<<NA, kHT, 0, s>>>(L.arrs, hist_part, hist_max, work, huff_lens, huff_maxd);
+  k_huff_lengths<<<dim3(NA, kHalvings - 1), kHT, 0, s>>>(work, huff_lens, huff_maxd);
   k_huff_codes<<<NA, kHT, 0, s>>>(work, huff_lens, huff_maxd);
   LCP_TIMED("chunk_bits", L.values * 4ull, s, {
     switch (chunk_log2) {

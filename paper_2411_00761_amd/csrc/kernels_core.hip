@@ -724,6 +724,64 @@ __global__ __launch_bounds__(kThreads) void k_t_recon(const int32_t* q_ref, int 
   if (bad) atomicOr(err, kErrCorrupt);
 }
 
+// A chain of J temporal frames, each coded against the one before it (the
+// first against q_ref): per slot the codes stay in registers while each
+// frame's residuals (int32, decoded in place in its output arrays) are added
+// and its float32 values written; only the last frame's codes are stored.
+__global__ __launch_bounds__(kThreads) void k_t_recon_chain(const int32_t* q_ref, int F,
+                                                            uint64_t n, GridDev g, ChainOut out,
+                                                            int J, int32_t* q_last, uint32_t* err,
+                                                            int vec) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  uint32_t bad = 0;
+  if (vec) {
+    for (uint64_t s4 = gid; s4 < n / 4; s4 += stride) {
+      for (int f = 0; f < F; f++) {
+        const int4 qr = reinterpret_cast<const int4*>(q_ref + (uint64_t)f * n)[s4];
+        int64_t q[4] = {qr.x, qr.y, qr.z, qr.w};
+        for (int j = 0; j < J; j++) {
+          float4* o = reinterpret_cast<float4*>(out.p[j][f]) + s4;
+          const int4 r = *reinterpret_cast<const int4*>(o);
+          q[0] += r.x;
+          q[1] += r.y;
+          q[2] += r.z;
+          q[3] += r.w;
+          float v[4];
+#pragma unroll
+          for (int u = 0; u < 4; u++) {
+            if (q[u] < -(int64_t)kQLimit || q[u] >= (int64_t)kQLimit) {
+              bad = 1;
+              q[u] = 0;
+            }
+            v[u] = reconstruct(q[u], g.eb_q[f], g.m[f]);
+          }
+          *o = make_float4(v[0], v[1], v[2], v[3]);
+        }
+        if (q_last)
+          reinterpret_cast<int4*>(q_last + (uint64_t)f * n)[s4] =
+              make_int4((int)q[0], (int)q[1], (int)q[2], (int)q[3]);
+      }
+    }
+  } else {
+    for (uint64_t s = gid; s < n; s += stride) {
+      for (int f = 0; f < F; f++) {
+        int64_t q = q_ref[(uint64_t)f * n + s];
+        for (int j = 0; j < J; j++) {
+          q += reinterpret_cast<const int32_t*>(out.p[j][f])[s];
+          if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
+            bad = 1;
+            q = 0;
+          }
+          out.p[j][f][s] = reconstruct(q, g.eb_q[f], g.m[f]);
+        }
+        if (q_last) q_last[(uint64_t)f * n + s] = (int32_t)q;
+      }
+    }
+  }
+  if (bad) atomicOr(err, kErrCorrupt);
+}
+
 // Copies the first min(size, stage) bytes (whole words) of every record into a
 // staging array, one workgroup per record.
 __global__ void k_gather_headers(const uint64_t* tab, int stage, uint8_t* dst) {
@@ -909,6 +967,17 @@ void launch_t_recon(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,
   LCP_TIMED("t_recon", n * (12ull * F + (q_slot ? 4ull * F : 0)), s,
             k_t_recon<<<grid_for(vec ? n / 4 : n, kThreads * 2, 1u << 16), kThreads, 0, s>>>(
                 q_ref, F, n, g, out, q_slot, err, vec));
+}
+
+void launch_t_recon_chain(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,
+                          const ChainOut& out, int J, int32_t* q_last, uint32_t* err,
+                          hipStream_t s) {
+  int vec = (n % 4 == 0) && al16(q_ref) && (!q_last || al16(q_last));
+  for (int j = 0; j < J; j++)
+    for (int f = 0; f < F; f++) vec = vec && al16(out.p[j][f]);
+  LCP_TIMED("t_recon", n * (8ull * F * J + 4ull * F + (q_last ? 4ull * F : 0)), s,
+            k_t_recon_chain<<<grid_for(vec ? n / 4 : n, kThreads * 2, 1u << 16), kThreads, 0, s>>>(
+                q_ref, F, n, g, out, J, q_last, err, vec));
 }
 
 void launch_gather_headers(const uint64_t* tab, int nrec, int stage, uint8_t* dst, hipStream_t s) {

@@ -6,6 +6,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <initializer_list>
 #include <vector>
 
 #include "../../include/lcp.h"
@@ -93,6 +94,7 @@ struct lcp_plan_s {
   // record offsets, then RB x 2F extent keys; ret_host is its pinned mirror
   unsigned long long *ret_dev, *ret_host;
   uint32_t* err;  // the error word (low half of ret_dev[0])
+  bool err_clean = false;  // the error word is known to be zero at the stream's tail
   uint8_t* rec_tmp;  // second record (temporal candidate)
   uint64_t rec_tmp_cap;
   uint32_t* ext_part;    // extent partials
@@ -180,11 +182,41 @@ lcp_status upload(const void* host, void* dev, size_t bytes, hipStream_t s) {
   return LCP_OK;
 }
 
+// Uploads tables that are adjacent, in the same order and at the same
+// relative offsets, on the host and on the device: the whole span in one
+// transfer when it is small, else each table's used part on its own.
+struct Part {
+  const void* host;
+  void* dev;
+  size_t bytes;  // used bytes
+};
+lcp_status upload_group(std::initializer_list<Part> parts, hipStream_t s) {
+  const Part& a = *parts.begin();
+  const Part& z = *(parts.end() - 1);
+  const size_t span = (size_t)(static_cast<const uint8_t*>(z.host) - static_cast<const uint8_t*>(a.host)) + z.bytes;
+  if (span <= 4 * (size_t)kInstallWords * 4) return upload(a.host, a.dev, (span + 3) & ~(size_t)3, s);
+  for (const Part& p : parts) {
+    lcp_status st = upload(p.host, p.dev, p.bytes, s);
+    if (st) return st;
+  }
+  return LCP_OK;
+}
+
 // Reads back the first `words` u64 of the return block and waits for the stream.
+// The error word is cleared right behind the read-back (on the GPU while the
+// host waits), so the next call need not start with a clearing launch.
 lcp_status read_ret(lcp_plan_s* P, size_t words, hipStream_t s) {
   HIP_OK(hipMemcpyAsync(P->ret_host, P->ret_dev, words * 8, hipMemcpyDeviceToHost, s));
+  launch_fill_u32(P->err, 1, 0u, s);
   HIP_OK(hipStreamSynchronize(s));
+  P->err_clean = true;
   return LCP_OK;
+}
+
+// Before kernels that may set the error word: zero it unless already known zero.
+void clear_err(lcp_plan_s* P, hipStream_t s) {
+  if (!P->err_clean) launch_fill_u32(P->err, 1, 0u, s);
+  P->err_clean = false;
 }
 uint32_t host_err(const lcp_plan_s* P) { return (uint32_t)(P->ret_host[0] & 0xFFFFFFFFull); }
 
@@ -260,8 +292,9 @@ lcp_status upload_segs(lcp_plan_s* P, int R, SegLayout* L, hipStream_t s) {
   p1[R] = l.blocks_1k;
   p2[R] = l.blocks_256;
   if (l.ntot > P->NB) return LCP_ERR_ARG;
-  lcp_status st = upload(P->seg_host, P->seg_dev, sizeof(SegDev) * R, s);
-  if (!st) st = upload(P->segpre_host, P->segpre_dev, sizeof(uint32_t) * 3 * (R + 1), s);
+  lcp_status st = upload_group({{P->seg_host, P->seg_dev, sizeof(SegDev) * R},
+                                 {P->segpre_host, P->segpre_dev, sizeof(uint32_t) * 3 * (R + 1)}},
+                                s);
   if (st) return st;
   *L = l;
   return LCP_OK;
@@ -275,7 +308,7 @@ lcp_status extent_batch(lcp_plan_s* P, int R, float (*lo)[kMaxF], float (*hi)[kM
   SegLayout L;
   lcp_status st = upload_segs(P, R, &L, s);
   if (st) return st;
-  launch_fill_u32(P->err, 1, 0u, s);
+  clear_err(P, s);
   launch_extent_b(P->seg_dev, P->segpre_dev, L.ext_blocks, R, F, P->ext_dev, P->ext_part,
                   P->err, (uint64_t)F * L.ntot * 4, s);
   const size_t ext_word0 = (size_t)(reinterpret_cast<unsigned long long*>(P->ext_dev) - P->ret_dev);
@@ -379,9 +412,10 @@ lcp_status enc_launch(lcp_plan_s* P, EncBuild& B, uint8_t* out, uint64_t cap, bo
   L.chunk_blocks = c;
   L.fixed_blocks = f;
   L.values = B.values;
-  lcp_status st = upload(P->earr_host, P->earr_dev, sizeof(EncArr) * NA, s);
-  if (!st) st = upload(P->erec_host, P->erec_dev, sizeof(EncRec) * B.R, s);
-  if (!st) st = upload(P->epre_host, P->epre_dev, sizeof(uint32_t) * 3 * (NA + 1), s);
+  lcp_status st = upload_group({{P->erec_host, P->erec_dev, sizeof(EncRec) * B.R},
+                                 {P->earr_host, P->earr_dev, sizeof(EncArr) * NA},
+                                 {P->epre_host, P->epre_dev, sizeof(uint32_t) * 3 * (NA + 1)}},
+                                s);
   if (st) return st;
   launch_encode(L, P->chunk_log2, P->work, P->chunk_words, P->hist_part, P->hist_max,
                 P->huff_lens, P->huff_maxd, out, cap, P->offs_dev, P->err, hist_done, s);
@@ -523,7 +557,7 @@ lcp_status compress_s_batch(lcp_plan_s* P, int R, const HostGrid (*g)[kMaxF],
       if ((st = enc_add(P, B, ArrIn{v_sup + (uint64_t)(f - 3) * ntot + o, 0, nullptr, n}, n, r, -1, 0)))
         return st;
   }
-  launch_fill_u32(P->err, 1, 0u, s);
+  clear_err(P, s);
   if ((st = enc_launch(P, B, out, cap, false, s))) return st;
   if (perm_dst) {
     bool any = false;
@@ -589,7 +623,7 @@ lcp_status compress_t(lcp_plan_s* P, const float* const* x, uint64_t n, const Re
     gd.eb2[f] = 2.0 * ref.grid[f].eb;
     gd.lim[f] = ldexp(1.0, ref.grid[f].E);
   }
-  launch_fill_u32(P->err, 1, 0u, s);
+  clear_err(P, s);
   launch_t_resid(fp, F, n, gd, P->ppool[ref.perm], P->qpool[ref.q], P->v_slot, q_new,
                  P->err, P->hist_part, P->hist_max, s);
   EncBuild B;
@@ -960,8 +994,9 @@ lcp_status decompress_s_batch(lcp_plan_s* P, const ParsedHdr* H, const lcp_blob*
       bytes += h.anb[a] + (a < 2 ? 8 : 4) * h.an[a];
     }
   }
-  lcp_status st = upload(P->dseg_host, P->dseg_dev, sizeof(DSegDev) * R, s);
-  if (!st) st = upload(P->dpre_host, P->dpre_dev, sizeof(uint32_t) * 2 * (R + 1), s);
+  lcp_status st = upload_group({{P->dseg_host, P->dseg_dev, sizeof(DSegDev) * R},
+                                 {P->dpre_host, P->dpre_dev, sizeof(uint32_t) * 2 * (R + 1)}},
+                                s);
   if (!st) st = decode_arrays(P, 0, A, cl, bytes, s);
   if (st) return st;
   const uint32_t* pre_slot = P->dpre_dev;
@@ -1045,7 +1080,7 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
       if (h.mode == 0 && first_in_batch(P, h.seq)) sa = r;
     }
   }
-  launch_fill_u32(P->err, 1, 0u, s);
+  clear_err(P, s);
   if (!multi) {
     // independent spatial records: batches of at most NB particles
     for (uint64_t j0 = 0; j0 < nf;) {
@@ -1084,8 +1119,22 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
     lcp_status st = decode_arrays(P, 0, A, cl, bytes, s);
     if (st) return st;
   }
-  // ---- reconstruction in stream order
+  // ---- reconstruction in stream order.  Consecutive temporal frames each coded
+  // against the previous one form a chain reconstructed in one pass; only the
+  // chain's last codes are kept (a later record can only reference the frame
+  // just before it or an anchor, which is spatial).
   int extra = A;  // staging slots for the id / count arrays of spatial frames
+  ChainOut chain;
+  int chain_len = 0, chain_ref = -1;
+  uint64_t chain_last = 0;
+  GridDev chain_g;
+  memset(&chain_g, 0, sizeof(chain_g));
+  auto flush_chain = [&]() {
+    if (chain_len)
+      launch_t_recon_chain(P->dqpool[chain_ref], F, H[chain_last].n, chain_g, chain, chain_len,
+                           P->dqpool[dq[chain_last]], P->err, s);
+    chain_len = 0;
+  };
   for (uint64_t j = 0; j < nf; j++) {
     const ParsedHdr& h = H[j];
     const uint64_t n = h.n;
@@ -1121,6 +1170,7 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
       if (st) return st;
     }
     if (h.mode == 0) {
+      flush_chain();
       const uint64_t B = h.B;
       unsigned __int128 tot = (unsigned __int128)h.bn[0] * h.bn[1] * h.bn[2];
       if (h.bn[0] == 0 || h.bn[1] == 0 || h.bn[2] == 0 || tot >= ((unsigned __int128)1 << 63))
@@ -1158,9 +1208,20 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
                               tmp32, s);
       launch_s_recon(P->flags, P->corner, B, F, n, h.k, gd, op, q_slot, P->err, s);
     } else {
-      launch_t_recon(P->dqpool[refq[j]], F, n, gd, op, q_slot, P->err, s);
+      const bool extend = chain_len > 0 && chain_len < kChainMax && j > 0 &&
+                          chain_last == j - 1 && refq[j] == dq[j - 1] && H[j - 1].n == n &&
+                          memcmp(&chain_g, &gd, sizeof(gd)) == 0;
+      if (!extend) {
+        flush_chain();
+        chain_ref = refq[j];
+        chain_g = gd;
+      }
+      for (int f = 0; f < F; f++) chain.p[chain_len][f] = outs[j].fields[f];
+      chain_len++;
+      chain_last = j;
     }
   }
+  flush_chain();
   }
   {
     lcp_status st = read_ret(P, 1, s);
@@ -1244,17 +1305,19 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   D.add(&P->scan_tmp, P->scan_tmp_n);
   D.add(&P->work, NA);
   D.add(&P->ret_dev, 2 + (uint64_t)RB + (uint64_t)RB * F);
+  // tables uploaded together are adjacent, with the same sizes as their host
+  // staging (seg + segpre, dseg + dpre, erec + earr + epre)
   D.add(&P->seg_dev, RB);
   D.add(&P->segpre_dev, 3 * ((uint64_t)RB + 1));
+  D.add(&P->dseg_dev, kMaxBatchFrames);
+  D.add(&P->dpre_dev, 2 * (kMaxBatchFrames + 1));
+  D.add(&P->erec_dev, RB);
+  D.add(&P->earr_dev, NA);
+  D.add(&P->epre_dev, 3 * (NA + 1));
   D.add(&P->rstart, (uint64_t)RB + 1);
   D.add(&P->Bs, RB);
   D.add(&P->permdst_dev, RB);
-  D.add(&P->dseg_dev, kMaxBatchFrames);
-  D.add(&P->dpre_dev, 2 * (kMaxBatchFrames + 1));
   D.add(&P->segbase, 3 * kMaxBatchFrames);
-  D.add(&P->earr_dev, NA);
-  D.add(&P->erec_dev, RB);
-  D.add(&P->epre_dev, 3 * (NA + 1));
   D.add(&P->rec_tmp, P->rec_tmp_cap);
   H.add(&P->ret_host, 2 + (size_t)RB + (size_t)RB * F);
   H.add(&P->hdr_host, (size_t)kHdrStage * kMaxBatchFrames);
@@ -1263,12 +1326,12 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   H.add(&P->prefix_host, 2 * (kMaxBatchArrays + 2 * kMaxBatchFrames));
   H.add(&P->seg_host, RB);
   H.add(&P->segpre_host, 3 * ((size_t)RB + 1));
-  H.add(&P->permdst_host, RB);
   H.add(&P->dseg_host, kMaxBatchFrames);
   H.add(&P->dpre_host, 2 * (kMaxBatchFrames + 1));
-  H.add(&P->earr_host, NA);
   H.add(&P->erec_host, RB);
+  H.add(&P->earr_host, NA);
   H.add(&P->epre_host, 3 * (NA + 1));
+  H.add(&P->permdst_host, RB);
 }
 
 // Resident stream state of multi-frame plans: the compressor's candidate and
@@ -1296,6 +1359,8 @@ void bind_scratch(lcp_plan_s* P, void* dev, void* host, hipStream_t s) {
   memset(P->seg_host, 0, sizeof(SegDev) * P->RB);
   launch_fill_u32(P->hist_part, P->hist_copies * kAlphabet, 0u, s);
   launch_fill_u32(reinterpret_cast<uint32_t*>(P->hist_max), 2 * P->hist_copies, 0u, s);
+  launch_fill_u32(P->err, 1, 0u, s);
+  P->err_clean = true;
 }
 
 lcp_status alloc_state(lcp_plan_s* P) {

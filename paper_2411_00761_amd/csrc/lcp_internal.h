@@ -221,6 +221,16 @@ void launch_t_recon(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,
 // reused as soon as this returns).
 constexpr int kInstallWords = 512;
 void launch_install(const void* src, void* dst, size_t bytes, hipStream_t s);
+// A chain of up to kChainMax temporal frames reconstructed in one pass:
+// out.p[j][f] holds frame j's int32 residuals and receives its values; frame
+// 0's reference codes are q_ref; q_last (nullable) receives the last frame's.
+constexpr int kChainMax = 16;
+struct ChainOut {
+  float* p[kChainMax][kMaxF];
+};
+void launch_t_recon_chain(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,
+                          const ChainOut& out, int J, int32_t* q_last, uint32_t* err,
+                          hipStream_t s);
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 // tab: nrec (device pointer, byte size) pairs; dst: nrec * stage bytes.
 void launch_gather_headers(const uint64_t* tab, int nrec, int stage, uint8_t* dst, hipStream_t s);
