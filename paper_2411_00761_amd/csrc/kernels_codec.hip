@@ -43,24 +43,14 @@ __device__ inline uint32_t array_of_block(const uint32_t* prefix, int A, uint32_
 }
 
 // ------------------------------------------------------------------ histogram
-// Each workgroup counts its share of one array in LDS and writes the whole
-// histogram as a partial (coalesced); a second kernel sums the partials per bin.
-// Lanes of a wave holding the same symbol are grouped by 13 ballots (one per
-// symbol bit); the lowest lane of each group adds the group's size, so a wave
-// of identical symbols (e.g. zero residuals) costs one LDS atomic, not 64.
-// Symbols below kPrivBins are counted in a private LDS histogram per wave (no
-// other wave touches it, and a wave's group leaders hold distinct symbols), the
-// rest in the workgroup's shared histogram with atomics.  A workgroup writes only
-// the bins up to the symbol of its largest value; the reduction reads each
-// partial up to the same bound.
+// Each workgroup counts its share of one array in LDS (wave_hist_add: the
+// wave's most common case, the first lane's symbol, in one update, the other
+// lanes by LDS atomics), symbols below kPrivBins in a private histogram per
+// wave and the rest in the workgroup's shared one, then adds the non-zero bins
+// up to its largest value's symbol into one of the array's spread copies in
+// global memory; k_huff_build sums the copies.
 constexpr int kPrivBins = 256;
 constexpr int kHistVals = 8;  // values per lane per iteration, loads issued together
-
-__device__ inline void hist_group_add(uint32_t* h, uint32_t* hp, uint32_t sym, bool valid,
-                                      uint64_t lt) {
-  (void)lt;
-  wave_hist_add(h, hp, kPrivBins, sym, valid);
-}
 
 __device__ inline int sym_bound(unsigned long long mx) {
   int e;
@@ -82,7 +72,6 @@ __global__ __launch_bounds__(kThreads) void k_hist(const EncArr* E, const uint32
   __syncthreads();
   uint32_t* hp = hpriv[wave_id()];
   uint64_t mx = 0;
-  const uint64_t lt = lanemask_lt();
   const uint64_t stride = (uint64_t)nb * kThreads * kHistVals;
   for (uint64_t base = ((uint64_t)lb * kThreads + wave_id() * kWave) * kHistVals; base < n;
        base += stride) {
@@ -96,7 +85,7 @@ __global__ __launch_bounds__(kThreads) void k_hist(const EncArr* E, const uint32
     for (int j = 0; j < kHistVals; j++) {
       int ex;
       const bool valid = base + (uint64_t)j * kWave + lane_id() < n;
-      hist_group_add(h, hp, (uint32_t)symbol_of(v[j], &ex), valid, lt);
+      wave_hist_add(h, hp, kPrivBins, (uint32_t)symbol_of(v[j], &ex), valid);
       mx = v[j] > mx ? v[j] : mx;
     }
   }

@@ -22,74 +22,117 @@ inline uint32_t grid_for(uint64_t n, uint64_t per_block, uint32_t cap = 1u << 20
   return (uint32_t)g;
 }
 
+// Every frame of a batch gets whole workgroups; a workgroup finds its frame by
+// binary search in a prefix table of per-frame workgroup counts (R + 1 entries).
+__device__ inline int seg_of_block(const uint32_t* pre, int R, uint32_t b) {
+  int lo = 0, hi = R - 1;  // largest r with pre[r] <= b
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (pre[mid] <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // ------------------------------------------------------------------ radix sort
+// Stable LSD radix sort of (key, value) pairs within each frame of a batch
+// (segments [off, off + n) of the SegDev table), 8-bit digits.  Tiles of
+// kRsTile elements never cross a frame.  The digit counts are laid out frame
+// by frame, then digit by digit, then tile by tile, so one exclusive scan gives
+// every (tile, digit) its output position inside its own frame.  The scatter
+// ranks a tile stably in LDS (ballots over the digit bits), places it there in
+// digit order, and writes each digit's run out contiguously.
 constexpr int kRsItems = 16;
 constexpr int kRsTile = kThreads * kRsItems;  // 4096 keys per tile
+static_assert(kRsTile == (int)kSortTile, "sort tile");
 
-__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint64_t* keys, uint64_t n,
-                                                         int shift, uint32_t* hist,
-                                                         uint32_t ntiles) {
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint64_t* keys, const SegDev* S,
+                                                         const uint32_t* pre, int R, int shift,
+                                                         uint32_t* hist) {
   __shared__ uint32_t cnt[kThreads / kWave][256];
   const int t = threadIdx.x, w = wave_id();
+  const int r = seg_of_block(pre, R, blockIdx.x);
+  const uint32_t lt = blockIdx.x - pre[r], nt = pre[r + 1] - pre[r];
+  const uint64_t base = S[r].off + (uint64_t)lt * kRsTile;
+  const uint64_t end = S[r].off + S[r].n;
   for (int j = 0; j < 4; j++) cnt[j][t] = 0;
   __syncthreads();
-  const uint64_t base = (uint64_t)blockIdx.x * kRsTile;
 #pragma unroll 4
   for (int j = 0; j < kRsItems; j++) {
     uint64_t i = base + (uint64_t)j * kThreads + t;
-    if (i < n) atomicAdd(&cnt[w][(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    if (i < end) atomicAdd(&cnt[w][(uint32_t)(keys[i] >> shift) & 255u], 1u);
   }
   __syncthreads();
-  hist[(uint64_t)t * ntiles + blockIdx.x] = cnt[0][t] + cnt[1][t] + cnt[2][t] + cnt[3][t];
+  hist[(uint64_t)pre[r] * 256 + (uint64_t)t * nt + lt] = cnt[0][t] + cnt[1][t] + cnt[2][t] + cnt[3][t];
 }
 
-// Stable scatter: elements keep their input order within a digit.  Each round
-// places 256 consecutive elements; a wave ranks equal digits by ballot (the 8
-// digit bits give each lane its set of peers) and waves are ordered by their
-// per-digit counts in LDS.
 __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* kin,
                                                             const uint32_t* vin, uint64_t* kout,
-                                                            uint32_t* vout, uint64_t n,
-                                                            int shift, const uint32_t* offs,
-                                                            uint32_t ntiles) {
-  __shared__ uint32_t base[256];
+                                                            uint32_t* vout, const SegDev* S,
+                                                            const uint32_t* pre, int R, int shift,
+                                                            const uint32_t* offs,
+                                                            uint64_t entries, uint64_t ntot) {
+  __shared__ uint64_t sk[kRsTile];
+  __shared__ uint32_t sv[kRsTile];
+  __shared__ uint32_t gbase[256], lstart[256], run[256];
   __shared__ uint32_t wcnt[kThreads / kWave][256];
+  __shared__ uint32_t sm[kThreads / kWave + 1];
   const int t = threadIdx.x, w = wave_id();
-  base[t] = offs[(uint64_t)t * ntiles + blockIdx.x];
-  const uint64_t tile0 = (uint64_t)blockIdx.x * kRsTile;
-  const uint64_t lt = lanemask_lt();
-  for (int r = 0; r < kRsItems; r++) {
-    const uint64_t i = tile0 + (uint64_t)r * kThreads + t;
-    const bool valid = i < n;
-    uint64_t key = valid ? kin[i] : 0;
-    uint32_t val = valid ? vin[i] : 0;
-    uint32_t d = (uint32_t)(key >> shift) & 255u;
+  const int r = seg_of_block(pre, R, blockIdx.x);
+  const uint32_t lt = blockIdx.x - pre[r], nt = pre[r + 1] - pre[r];
+  const uint64_t tile0 = S[r].off + (uint64_t)lt * kRsTile;
+  const uint64_t rem = S[r].n - (uint64_t)lt * kRsTile;
+  const uint32_t cnt = rem < (uint64_t)kRsTile ? (uint32_t)rem : (uint32_t)kRsTile;
+  // this tile's output start and element count for digit t
+  const uint64_t e = (uint64_t)pre[r] * 256 + (uint64_t)t * nt + lt;
+  const uint32_t g = offs[e];
+  const uint32_t c = (uint32_t)((e + 1 < entries ? (uint64_t)offs[e + 1] : ntot) - g);
+  uint32_t tot;
+  const uint32_t ls = block_incl_scan(c, sm, &tot) - c;
+  gbase[t] = g;
+  lstart[t] = ls;
+  run[t] = 0;
+  __syncthreads();
+  const uint64_t lmask = lanemask_lt();
+  for (int rd = 0; rd < kRsItems; rd++) {
+    const uint32_t li = (uint32_t)rd * kThreads + t;
+    const bool valid = li < cnt;
+    const uint64_t key = valid ? kin[tile0 + li] : 0;
+    const uint32_t val = valid ? vin[tile0 + li] : 0;
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
 #pragma unroll
     for (int j = 0; j < kThreads / kWave; j++) wcnt[j][t] = 0;
     __syncthreads();
     uint64_t peers = __ballot(valid);
 #pragma unroll
     for (int b = 0; b < 8; b++) {
-      uint64_t bal = __ballot((d >> b) & 1u);
+      const uint64_t bal = __ballot((d >> b) & 1u);
       peers &= ((d >> b) & 1u) ? bal : ~bal;
     }
-    uint32_t rank = (uint32_t)__popcll(peers & lt);
+    const uint32_t rank = (uint32_t)__popcll(peers & lmask);
     if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
     __syncthreads();
     if (valid) {
-      uint32_t off = base[d] + rank;
-      for (int j = 0; j < w; j++) off += wcnt[j][d];
-      if (off < n) {
-        kout[off] = key;
-        vout[off] = val;
-      }
+      uint32_t pos = lstart[d] + run[d] + rank;
+      for (int j = 0; j < w; j++) pos += wcnt[j][d];
+      sk[pos] = key;
+      sv[pos] = val;
     }
     __syncthreads();
     uint32_t add = 0;
 #pragma unroll
     for (int j = 0; j < kThreads / kWave; j++) add += wcnt[j][t];
-    base[t] += add;
+    run[t] += add;
     __syncthreads();
+  }
+  // the tile in digit order: consecutive slots of one digit go to consecutive
+  // output positions
+  for (uint32_t i = t; i < cnt; i += kThreads) {
+    const uint64_t key = sk[i];
+    const uint32_t d = (uint32_t)(key >> shift) & 255u;
+    const uint64_t pos = (uint64_t)gbase[d] + (i - lstart[d]);
+    kout[pos] = key;
+    vout[pos] = sv[i];
   }
 }
 
@@ -271,17 +314,6 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
 }
 
 // ------------------------------------------------------------------ spatial batch
-// Every frame of a batch gets whole workgroups; a workgroup finds its frame by
-// binary search in a prefix table of per-frame workgroup counts (R + 1 entries).
-__device__ inline int seg_of_block(const uint32_t* pre, int R, uint32_t b) {
-  int lo = 0, hi = R - 1;  // largest r with pre[r] <= b
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (pre[mid] <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
 
 __global__ __launch_bounds__(kThreads) void k_extent_b(const SegDev* S, const uint32_t* pre, int R,
                                                        uint32_t* part, uint32_t* err) {
@@ -371,24 +403,29 @@ __global__ __launch_bounds__(kThreads) void k_extent_final_b(const uint32_t* par
   }
 }
 
-// Eq. 5 and Eq. 6 per particle; the frame tag above the block id keeps frames
-// apart in the batch-wide sort.  vals = index within the frame.
+// Eq. 5 and Eq. 6 per particle.  vals = index within the frame; prel = the
+// particle's three offsets inside its block (k <= 16 bits each), in input
+// order, so the slot pass gathers one word per slot instead of three floats.
 __global__ __launch_bounds__(kThreads) void k_quant_key_b(const SegDev* S, const uint32_t* pre,
-                                                          int R, uint64_t* keys, uint32_t* vals) {
+                                                          int R, uint64_t* keys, uint32_t* vals,
+                                                          uint64_t* prel) {
   const int r = seg_of_block(pre, R, blockIdx.x);
   const SegDev& g = S[r];
   const uint64_t n = g.n;
   const uint64_t i0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg1k;
   const int k = g.k;
+  const uint64_t pm = (1ull << k) - 1ull;
 #pragma unroll
   for (int j = 0; j < (int)(kSeg1k / kThreads); j++) {
     const uint64_t i = i0 + (uint64_t)j * kThreads + threadIdx.x;
     if (i < n) {
-      uint64_t b0 = (uint64_t)quantise(g.x[0][i], g.m[0], g.inv[0]) >> k;
-      uint64_t b1 = (uint64_t)quantise(g.x[1][i], g.m[1], g.inv[1]) >> k;
-      uint64_t b2 = (uint64_t)quantise(g.x[2][i], g.m[2], g.inv[2]) >> k;
-      keys[g.off + i] = g.key_hi | (b0 + g.bn0 * (b1 + g.bn1 * b2));  // Eq. 6, x fastest
+      const uint64_t q0 = (uint64_t)quantise(g.x[0][i], g.m[0], g.inv[0]);
+      const uint64_t q1 = (uint64_t)quantise(g.x[1][i], g.m[1], g.inv[1]);
+      const uint64_t q2 = (uint64_t)quantise(g.x[2][i], g.m[2], g.inv[2]);
+      const uint64_t b0 = q0 >> k, b1 = q1 >> k, b2 = q2 >> k;
+      keys[g.off + i] = b0 + g.bn0 * (b1 + g.bn1 * b2);  // Eq. 6, x fastest
       vals[g.off + i] = (uint32_t)i;
+      prel[g.off + i] = (q0 & pm) | ((q1 & pm) << 16) | ((q2 & pm) << 32);
     }
   }
 }
@@ -414,7 +451,7 @@ __global__ __launch_bounds__(kThreads) void k_runs_write_b(const uint64_t* keys,
                                                            uint64_t* ids, uint32_t* starts,
                                                            uint32_t* rstart, uint32_t* Bs) {
   const int r = seg_of_block(pre, R, blockIdx.x);
-  const uint64_t n = S[r].n, off = S[r].off, mask = S[r].id_mask;
+  const uint64_t n = S[r].n, off = S[r].off;
   const uint64_t i0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg1k;
 #pragma unroll
   for (int j = 0; j < (int)(kSeg1k / kThreads); j++) {
@@ -423,7 +460,7 @@ __global__ __launch_bounds__(kThreads) void k_runs_write_b(const uint64_t* keys,
     const uint64_t g = off + i;
     if (i == 0 || keys[g] != keys[g - 1]) {
       const uint32_t b = scan[g] - 1;
-      ids[b] = keys[g] & mask;
+      ids[b] = keys[g];
       starts[b] = (uint32_t)g;
       if (i == 0) rstart[r] = b;
     }
@@ -467,22 +504,23 @@ __global__ __launch_bounds__(kThreads) void k_block_syms_b(const uint64_t* ids,
 // predecessor for the delta (mod p), which restarts at each frame's first slot.
 __global__ __launch_bounds__(kThreads) void k_slot_syms_b(const SegDev* S, const uint32_t* pre,
                                                           int R, int F, const uint32_t* perm,
-                                                          uint64_t ntot, uint32_t* v_rel,
-                                                          uint32_t* v_sup, int32_t* q_slot) {
+                                                          const uint64_t* prel, uint64_t ntot,
+                                                          uint32_t* v_rel, uint32_t* v_sup,
+                                                          int32_t* q_slot) {
   __shared__ uint32_t rel[3][kThreads + 1];
   const int r = seg_of_block(pre, R, blockIdx.x);
   const SegDev& g = S[r];
   const uint64_t n = g.n, off = g.off;
   const uint64_t s0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg256;
   const uint64_t s = s0 + threadIdx.x;
-  const uint32_t pm = (1u << g.k) - 1u;
   const bool valid = s < n;
   const uint32_t i = valid ? perm[off + s] : 0;
   if (valid) {
-    for (int f = 0; f < F; f++) {
+    const uint64_t pr = prel[off + i];
+    for (int d = 0; d < 3; d++) rel[d][threadIdx.x + 1] = (uint32_t)(pr >> (16 * d)) & 0xFFFFu;
+    for (int f = q_slot ? 0 : 3; f < F; f++) {
       int64_t q = quantise(g.x[f][i], g.m[f], g.inv[f]);
-      if (f < 3) rel[f][threadIdx.x + 1] = (uint32_t)q & pm;
-      else v_sup[(uint64_t)(f - 3) * ntot + off + s] = (uint32_t)q;
+      if (f >= 3) v_sup[(uint64_t)(f - 3) * ntot + off + s] = (uint32_t)q;
       if (q_slot) q_slot[(uint64_t)f * ntot + off + s] = (int32_t)q;
     }
   }
@@ -490,10 +528,11 @@ __global__ __launch_bounds__(kThreads) void k_slot_syms_b(const SegDev* S, const
     if (s0 == 0) {
       rel[0][0] = rel[1][0] = rel[2][0] = 0;
     } else {
-      const uint32_t ip = perm[off + s0 - 1];
-      for (int d = 0; d < 3; d++) rel[d][0] = (uint32_t)quantise(g.x[d][ip], g.m[d], g.inv[d]) & pm;
+      const uint64_t pr = prel[off + perm[off + s0 - 1]];
+      for (int d = 0; d < 3; d++) rel[d][0] = (uint32_t)(pr >> (16 * d)) & 0xFFFFu;
     }
   }
+  const uint32_t pm = (1u << g.k) - 1u;
   __syncthreads();
   if (valid)
     for (int d = 0; d < 3; d++)
@@ -824,9 +863,10 @@ void launch_extent_b(const SegDev* S, const uint32_t* pre_ext, uint32_t ext_bloc
 }
 
 void launch_quant_key_b(const SegDev* S, const uint32_t* pre_1k, uint32_t blocks, int R,
-                        uint64_t* keys, uint32_t* vals, uint64_t ntot, hipStream_t s) {
-  LCP_TIMED("quant_key", ntot * (12 + 12), s,
-            k_quant_key_b<<<blocks, kThreads, 0, s>>>(S, pre_1k, R, keys, vals));
+                        uint64_t* keys, uint32_t* vals, uint64_t* prel, uint64_t ntot,
+                        hipStream_t s) {
+  LCP_TIMED("quant_key", ntot * (12 + 20), s,
+            k_quant_key_b<<<blocks, kThreads, 0, s>>>(S, pre_1k, R, keys, vals, prel));
 }
 
 void launch_runs_b(const uint64_t* keys, const SegDev* S, const uint32_t* pre_1k, uint32_t blocks,
@@ -845,12 +885,12 @@ void launch_block_syms_b(const uint64_t* ids, const uint32_t* starts, const uint
 }
 
 void launch_slot_syms_b(const SegDev* S, const uint32_t* pre_256, uint32_t blocks, int R, int F,
-                        const uint32_t* perm, uint64_t ntot, uint32_t* v_rel, uint32_t* v_sup,
-                        int32_t* q_slot, hipStream_t s) {
-  uint64_t bytes = ntot * (4 + 4ull * F + 4ull * F + (q_slot ? 4ull * F : 0));
+                        const uint32_t* perm, const uint64_t* prel, uint64_t ntot, uint32_t* v_rel,
+                        uint32_t* v_sup, int32_t* q_slot, hipStream_t s) {
+  uint64_t bytes = ntot * (4 + 8 + 4ull * (F - 3) + 4ull * F + (q_slot ? 16ull * F : 0));
   LCP_TIMED("slot_syms", bytes, s,
-            k_slot_syms_b<<<blocks, kThreads, 0, s>>>(S, pre_256, R, F, perm, ntot, v_rel, v_sup,
-                                                     q_slot));
+            k_slot_syms_b<<<blocks, kThreads, 0, s>>>(S, pre_256, R, F, perm, prel, ntot, v_rel,
+                                                     v_sup, q_slot));
 }
 
 void launch_copy_perm_b(const uint32_t* perm, const SegDev* S, const uint32_t* pre_1k,
@@ -858,20 +898,21 @@ void launch_copy_perm_b(const uint32_t* perm, const SegDev* S, const uint32_t* p
   k_copy_perm_b<<<blocks, kThreads, 0, s>>>(perm, S, pre_1k, R, dst);
 }
 
-int radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint64_t n, int bits,
+int radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, const SegDev* S,
+               const uint32_t* pre_tile, uint32_t ntiles, int R, uint64_t ntot, int bits,
                uint32_t* hist, uint32_t* tmp32, hipStream_t s) {
-  const uint32_t ntiles = (uint32_t)((n + kRsTile - 1) / kRsTile);
+  const uint64_t entries = (uint64_t)ntiles * 256;
   int cur = 0;
   for (int shift = 0; shift < bits; shift += 8) {
     uint64_t* kin = cur ? k1 : k0;
     uint32_t* vin = cur ? v1 : v0;
     uint64_t* kout = cur ? k0 : k1;
     uint32_t* vout = cur ? v0 : v1;
-    k_radix_hist<<<ntiles, kThreads, 0, s>>>(kin, n, shift, hist, ntiles);
-    scan_device<uint32_t>(hist, (uint64_t)ntiles * 256, nullptr, true, tmp32, s);
-    LCP_TIMED("radix_scatter", n * 24, s,
-              k_radix_scatter<<<ntiles, kThreads, 0, s>>>(kin, vin, kout, vout, n, shift, hist,
-                                                          ntiles));
+    k_radix_hist<<<ntiles, kThreads, 0, s>>>(kin, S, pre_tile, R, shift, hist);
+    scan_device<uint32_t>(hist, entries, nullptr, true, tmp32, s);
+    LCP_TIMED("radix_scatter", ntot * 24, s,
+              k_radix_scatter<<<ntiles, kThreads, 0, s>>>(kin, vin, kout, vout, S, pre_tile, R,
+                                                          shift, hist, entries, ntot));
     cur ^= 1;
   }
   return cur;

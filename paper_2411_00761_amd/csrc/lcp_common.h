@@ -110,25 +110,22 @@ __device__ inline T block_incl_scan(T v, T* sm, T* total) {
   return r;
 }
 
-// Adds the symbols of the active lanes of a wave to a histogram.  Lanes holding
-// the same symbol are grouped by peeling (the first pending lane's symbol is
-// broadcast and its peers found with one ballot); one lane per group adds the
-// group size, to the wave-private bins `priv` for symbols below n_priv, else
-// with an atomic to `shared`.  Runs once per distinct symbol in the wave.
+// Adds the symbols of the active lanes of a wave to a histogram.  The first
+// active lane's symbol is broadcast and its peers found with one ballot; one
+// lane adds that group's size (a wave of identical symbols, e.g. zero
+// residuals, costs one update) and every other lane adds 1 with an LDS atomic.
+// Symbols below n_priv go to the wave-private bins `priv`, the rest to
+// `shared`.
 __device__ inline void wave_hist_add(uint32_t* shared, uint32_t* priv, int n_priv, uint32_t sym,
                                      bool valid) {
-  uint64_t todo = __ballot(valid);
-  while (todo) {
-    const int l = __ffsll((long long)todo) - 1;
-    const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)sym, l);
-    const uint64_t m = __ballot(sym == s0) & todo;
-    if (lane_id() == l) {
-      const uint32_t cnt = (uint32_t)__popcll(m);
-      if (s0 < (uint32_t)n_priv) priv[s0] += cnt;
-      else atomicAdd(&shared[s0], cnt);
-    }
-    todo &= ~m;
-  }
+  const uint64_t todo = __ballot(valid);
+  if (!todo) return;
+  const int l = __ffsll((long long)todo) - 1;
+  const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)sym, l);
+  const uint64_t m = __ballot(valid && sym == s0);
+  uint32_t* bins = sym < (uint32_t)n_priv ? priv : shared;
+  if (lane_id() == l) atomicAdd(&bins[sym], (uint32_t)__popcll(m));
+  else if (valid && sym != s0) atomicAdd(&bins[sym], 1u);
 }
 
 // Sortable unsigned image of a float (monotone: a < b  <=>  key(a) < key(b)).

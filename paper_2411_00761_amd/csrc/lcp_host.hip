@@ -85,7 +85,7 @@ struct lcp_plan_s {
   size_t scratch_bytes = 0, host_bytes = 0, state_bytes = 0;
 
   // scratch (batch-wide arrays hold NB slots)
-  uint64_t *keys0, *keys1, *ids, *v_id, *v_cnt;
+  uint64_t *keys0, *keys1, *ids, *v_id, *v_cnt, *prel;
   uint32_t *vals0, *vals1, *hist, *flags, *starts, *v_slot, *chunk_words, *lut, *corner;
   uint64_t* scan_tmp;
   size_t scan_tmp_n;
@@ -104,7 +104,7 @@ struct lcp_plan_s {
   uint32_t* huff_maxd;
   // spatial batch tables (pinned host staging + device mirrors)
   SegDev *seg_host, *seg_dev;
-  uint32_t *segpre_host, *segpre_dev;  // [3][RB + 1]
+  uint32_t *segpre_host, *segpre_dev;  // [4][RB + 1]
   uint32_t* ext_dev;                   // [RB][2F] extent keys (in ret_dev)
   uint32_t *rstart, *Bs;               // [RB + 1], [RB]
   uint32_t **permdst_host, **permdst_dev;
@@ -268,7 +268,7 @@ GridDev to_dev(const HostGrid* g, int F) {
 // ------------------------------------------------------------------ spatial batch tables
 // The caller fills seg_host[r].x and .n; frames are placed back to back.
 struct SegLayout {
-  uint32_t ext_blocks = 0, blocks_1k = 0, blocks_256 = 0;
+  uint32_t ext_blocks = 0, blocks_1k = 0, blocks_256 = 0, tiles = 0;
   uint64_t ntot = 0;
 };
 
@@ -276,6 +276,7 @@ lcp_status upload_segs(lcp_plan_s* P, int R, SegLayout* L, hipStream_t s) {
   uint32_t* pe = P->segpre_host;
   uint32_t* p1 = pe + (R + 1);
   uint32_t* p2 = p1 + (R + 1);
+  uint32_t* pt = p2 + (R + 1);
   SegLayout l;
   for (int r = 0; r < R; r++) {
     SegDev& g = P->seg_host[r];
@@ -284,16 +285,19 @@ lcp_status upload_segs(lcp_plan_s* P, int R, SegLayout* L, hipStream_t s) {
     pe[r] = l.ext_blocks;
     p1[r] = l.blocks_1k;
     p2[r] = l.blocks_256;
+    pt[r] = l.tiles;
     l.ext_blocks += seg_ext_blocks(g.n);
     l.blocks_1k += (uint32_t)((g.n + kSeg1k - 1) / kSeg1k);
     l.blocks_256 += (uint32_t)((g.n + kSeg256 - 1) / kSeg256);
+    l.tiles += (uint32_t)((g.n + kSortTile - 1) / kSortTile);
   }
   pe[R] = l.ext_blocks;
   p1[R] = l.blocks_1k;
   p2[R] = l.blocks_256;
+  pt[R] = l.tiles;
   if (l.ntot > P->NB) return LCP_ERR_ARG;
   lcp_status st = upload_group({{P->seg_host, P->seg_dev, sizeof(SegDev) * R},
-                                 {P->segpre_host, P->segpre_dev, sizeof(uint32_t) * 3 * (R + 1)}},
+                                 {P->segpre_host, P->segpre_dev, sizeof(uint32_t) * 4 * (R + 1)}},
                                 s);
   if (st) return st;
   *L = l;
@@ -490,45 +494,19 @@ lcp_status compress_s_batch(lcp_plan_s* P, int R, const HostGrid (*g)[kMaxF],
     hdr[r] = make_hdr(0, F, k, P->chunk_log2, F + 2, sg.n, seq0 + r, ~0ull, g[r]);
     for (int d = 0; d < 3; d++) hdr[r].bn[d] = (uint32_t)bn[d];
   }
-  // Sort runs: consecutive frames whose tags fit above their block-id bits in
-  // 64-bit keys are sorted together (normally the whole batch).
-  struct Run {
-    int r0, r1;
-  };
-  std::vector<Run> runs;
   int sort_bits = 0;
-  for (int r0 = 0; r0 < R;) {
-    int r1 = r0 + 1, kmax = kb[r0];
-    while (r1 < R) {
-      int km = kb[r1] > kmax ? kb[r1] : kmax;
-      if (km + bitwidth64((uint64_t)(r1 - r0)) > 64) break;
-      kmax = km;
-      r1++;
-    }
-    for (int r = r0; r < r1; r++) {
-      P->seg_host[r].key_hi = (r == r0) ? 0ull : ((uint64_t)(r - r0) << kmax);
-      P->seg_host[r].id_mask = kmax ? (~0ull >> (64 - kmax)) : 0ull;
-    }
-    int bits = kmax + bitwidth64((uint64_t)(r1 - r0 - 1));
-    sort_bits = bits > sort_bits ? bits : sort_bits;
-    runs.push_back({r0, r1});
-    r0 = r1;
-  }
+  for (int r = 0; r < R; r++) sort_bits = kb[r] > sort_bits ? kb[r] : sort_bits;
   SegLayout L;
   lcp_status st = upload_segs(P, R, &L, s);
   if (st) return st;
   const uint64_t ntot = L.ntot;
   const uint32_t* pre_1k = P->segpre_dev + (R + 1);
   const uint32_t* pre_256 = P->segpre_dev + 2 * (R + 1);
-  launch_quant_key_b(P->seg_dev, pre_1k, L.blocks_1k, R, P->keys0, P->vals0, ntot, s);
-  int cur = 0;
+  launch_quant_key_b(P->seg_dev, pre_1k, L.blocks_1k, R, P->keys0, P->vals0, P->prel, ntot, s);
   uint32_t* tmp32 = reinterpret_cast<uint32_t*>(P->scan_tmp);
-  for (const Run& ru : runs) {
-    const uint64_t o = P->seg_host[ru.r0].off;
-    const uint64_t m = P->seg_host[ru.r1 - 1].off + P->seg_host[ru.r1 - 1].n - o;
-    cur = radix_sort(P->keys0 + o, P->vals0 + o, P->keys1 + o, P->vals1 + o, m, sort_bits,
-                     P->hist, tmp32, s);
-  }
+  const int cur = radix_sort(P->keys0, P->vals0, P->keys1, P->vals1, P->seg_dev,
+                             P->segpre_dev + 3 * (R + 1), L.tiles, R, ntot, sort_bits, P->hist,
+                             tmp32, s);
   const uint64_t* keys = cur ? P->keys1 : P->keys0;
   const uint32_t* perm = cur ? P->vals1 : P->vals0;
   launch_runs_b(keys, P->seg_dev, pre_1k, L.blocks_1k, R, ntot, P->flags, P->ids, P->starts,
@@ -536,7 +514,8 @@ lcp_status compress_s_batch(lcp_plan_s* P, int R, const HostGrid (*g)[kMaxF],
   launch_block_syms_b(P->ids, P->starts, P->rstart, R, P->seg_dev, ntot, P->v_id, P->v_cnt, s);
   uint32_t* v_rel = P->v_slot;
   uint32_t* v_sup = P->v_slot + 3 * ntot;
-  launch_slot_syms_b(P->seg_dev, pre_256, L.blocks_256, R, F, perm, ntot, v_rel, v_sup, q_slot, s);
+  launch_slot_syms_b(P->seg_dev, pre_256, L.blocks_256, R, F, perm, P->prel, ntot, v_rel, v_sup,
+                     q_slot, s);
 
   EncBuild B;
   B.R = R;
@@ -1266,7 +1245,7 @@ struct Layout {
 void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   const uint64_t N = P->N, NB = P->NB;
   const int F = P->F, RB = P->RB;
-  const uint64_t ntiles = (NB + 4095) / 4096;
+  const uint64_t ntiles = (NB + kSortTile - 1) / kSortTile + RB;  // tiles never cross frames
   P->NAmax = RB * (F + 2);
   const uint64_t NA = (uint64_t)P->NAmax;
   // spread histogram copies: enc_hist_copies(n) <= 1 + (1 + n / 8192) / 16 per
@@ -1284,6 +1263,7 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   D.add(&P->ids, NB);
   D.add(&P->v_id, NB);
   D.add(&P->v_cnt, NB);
+  D.add(&P->prel, NB);
   D.add(&P->vals0, NB);
   D.add(&P->vals1, NB);
   D.add(&P->hist, 256 * ntiles);
@@ -1308,7 +1288,7 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   // tables uploaded together are adjacent, with the same sizes as their host
   // staging (seg + segpre, dseg + dpre, erec + earr + epre)
   D.add(&P->seg_dev, RB);
-  D.add(&P->segpre_dev, 3 * ((uint64_t)RB + 1));
+  D.add(&P->segpre_dev, 4 * ((uint64_t)RB + 1));
   D.add(&P->dseg_dev, kMaxBatchFrames);
   D.add(&P->dpre_dev, 2 * (kMaxBatchFrames + 1));
   D.add(&P->erec_dev, RB);
@@ -1325,7 +1305,7 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   H.add(&P->arrtab_host, kMaxBatchArrays + 2 * kMaxBatchFrames);
   H.add(&P->prefix_host, 2 * (kMaxBatchArrays + 2 * kMaxBatchFrames));
   H.add(&P->seg_host, RB);
-  H.add(&P->segpre_host, 3 * ((size_t)RB + 1));
+  H.add(&P->segpre_host, 4 * ((size_t)RB + 1));
   H.add(&P->dseg_host, kMaxBatchFrames);
   H.add(&P->dpre_host, 2 * (kMaxBatchFrames + 1));
   H.add(&P->erec_host, RB);

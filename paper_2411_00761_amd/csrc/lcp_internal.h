@@ -85,8 +85,6 @@ struct SegDev {
   double inv[kMaxF];
   uint64_t n, off;
   uint64_t bn0, bn1;  // Eq. 6 block grid
-  uint64_t key_hi;    // frame tag placed above the block-id bits of its sort keys
-  uint64_t id_mask;   // block-id bits of a key
   int k, pad;
 };
 // One frame of a spatial decode batch (device table): frame r owns slots
@@ -151,13 +149,15 @@ void plan_bind(lcp_plan_s* P, void* dev, void* host, hipStream_t s);
 
 // ---- kernels_core.hip ----
 // Spatial batch front end.  pre_* are device prefix tables (R + 1 entries) of
-// the workgroups each frame gets: seg_ext_blocks(n), ceil(n / kSeg1k) and
-// ceil(n / kSeg256).  ext receives R x 2F sortable keys (min, max per field).
+// the workgroups each frame gets: seg_ext_blocks(n), ceil(n / kSeg1k),
+// ceil(n / kSeg256) and ceil(n / kSortTile).  ext receives R x 2F sortable keys (min, max per field).
 void launch_extent_b(const SegDev* S, const uint32_t* pre_ext, uint32_t ext_blocks, int R, int F,
                      uint32_t* ext, uint32_t* part, uint32_t* err, uint64_t bytes, hipStream_t s);
+// prel receives each particle's three in-block offsets (16 bits apart), input order.
 void launch_quant_key_b(const SegDev* S, const uint32_t* pre_1k, uint32_t blocks, int R,
-                        uint64_t* keys, uint32_t* vals, uint64_t ntot, hipStream_t s);
-// Non-empty blocks of every frame: ids (frame tag removed), global start slots,
+                        uint64_t* keys, uint32_t* vals, uint64_t* prel, uint64_t ntot,
+                        hipStream_t s);
+// Non-empty blocks of every frame: ids, global start slots,
 // rstart[r] (first block of frame r; rstart[R] = all blocks) and Bs[r].
 void launch_runs_b(const uint64_t* keys, const SegDev* S, const uint32_t* pre_1k, uint32_t blocks,
                    int R, uint64_t ntot, uint32_t* flags_scan, uint64_t* ids, uint32_t* starts,
@@ -168,15 +168,19 @@ void launch_block_syms_b(const uint64_t* ids, const uint32_t* starts, const uint
                          hipStream_t s);
 // v_rel: [3][ntot], v_sup: [F-3][ntot]; q_slot (nullable): [F][ntot].
 void launch_slot_syms_b(const SegDev* S, const uint32_t* pre_256, uint32_t blocks, int R, int F,
-                        const uint32_t* perm, uint64_t ntot, uint32_t* v_rel, uint32_t* v_sup,
-                        int32_t* q_slot, hipStream_t s);
+                        const uint32_t* perm, const uint64_t* prel, uint64_t ntot, uint32_t* v_rel,
+                        uint32_t* v_sup, int32_t* q_slot, hipStream_t s);
 // dst[r] (device table of device pointers, entries may be null) <- perm slice of frame r.
 void launch_copy_perm_b(const uint32_t* perm, const SegDev* S, const uint32_t* pre_1k,
                         uint32_t blocks, int R, uint32_t* const* dst, hipStream_t s);
 
-// Stable LSD radix sort of (key, value) by the low `bits` key bits.  Returns the
-// buffer index (0: k0/v0, 1: k1/v1) that holds the result.
-int radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, uint64_t n, int bits,
+// Stable LSD radix sort of (key, value) by the low `bits` key bits, within
+// each frame of the SegDev table (pre_tile: ceil(n / kSortTile) tiles per
+// frame, ntiles in all; hist: 256 * ntiles u32).  Returns the buffer index
+// (0: k0/v0, 1: k1/v1) that holds the result.
+constexpr uint32_t kSortTile = 4096;
+int radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, const SegDev* S,
+               const uint32_t* pre_tile, uint32_t ntiles, int R, uint64_t ntot, int bits,
                uint32_t* hist, uint32_t* tmp32, hipStream_t s);
 template <typename T>
 void scan_device(T* data, uint64_t n, const uint32_t* n_dev, bool exclusive, T* tmp,

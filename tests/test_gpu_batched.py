@@ -81,9 +81,9 @@ def test_batches_split_by_particle_count(lcp):
     check_batch(lcp, mixed_frames(), lcp.EB_ABS, 1e-3, 7)
 
 
-def test_batch_with_several_sort_runs(lcp):
-    """20 bits of block id per axis at k = 0: 32 frame tags do not fit above the
-    60 id bits of a 64-bit key, so the batch is sorted in two runs."""
+def test_batch_with_wide_keys(lcp):
+    """20 bits of block id per axis at k = 0: 60-bit keys, eight radix passes,
+    32 frames sorted side by side within their own segments."""
     xs = [datagen.uniform_frame(100, hi=1.0e6, seed=200 + j) for j in range(32)]
     check_batch(lcp, xs, lcp.EB_ABS, 0.5, 0, max_batch_particles=3200, max_batch_frames=32)
 
