@@ -147,7 +147,7 @@ __device__ inline uint32_t block_max_u32(uint32_t v, uint32_t* misc) {
 // kOffLens; returns the longest code (block-uniform).
 constexpr int kPer = (kAlphabet + kHT - 1) / kHT;  // 5 symbols per thread
 
-__device__ uint32_t huff_build(const uint32_t* c, uint8_t* smb, uint8_t* lens_g) {
+__device__ uint32_t huff_build(const uint32_t* c, int nsym, uint8_t* smb, uint8_t* lens_g) {
   uint64_t* sm64 = reinterpret_cast<uint64_t*>(smb);
   uint32_t* leafw = reinterpret_cast<uint32_t*>(smb);
   uint16_t* dist = reinterpret_cast<uint16_t*>(smb);
@@ -183,7 +183,7 @@ __device__ uint32_t huff_build(const uint32_t* c, uint8_t* smb, uint8_t* lens_g)
   if (U == 1) {
     uint32_t only = (uint32_t)(sm64[0] & 0x1FFFu);
     __syncthreads();
-    for (int s = t; s < kAlphabet; s += kHT) {
+    for (int s = t; s < nsym; s += kHT) {
       const uint8_t l = (uint32_t)s == only ? 1 : 0;
       lens_g[s] = l;
       lens_l[s] = l;
@@ -307,7 +307,7 @@ __device__ uint32_t huff_build(const uint32_t* c, uint8_t* smb, uint8_t* lens_g)
     }
     __syncthreads();
   }
-  for (int s = t; s < kAlphabet; s += kHT) {
+  for (int s = t; s < nsym; s += kHT) {
     lens_g[s] = 0;
     lens_l[s] = 0;
   }
@@ -330,7 +330,8 @@ __device__ uint32_t huff_build(const uint32_t* c, uint8_t* smb, uint8_t* lens_g)
 // Canonical codes from code lengths in LDS: shorter first, ties by symbol
 // (RFC 1951 order), and the table of used symbols.  wcnt: kHT / kWave * 16
 // u32 and misc: 64 u32 of LDS scratch.
-__device__ void huff_codes(ArrWork& w, const uint8_t* lens, uint32_t* wcnt, uint32_t* misc) {
+__device__ void huff_codes(ArrWork& w, int nsym, const uint8_t* lens, uint32_t* wcnt,
+                           uint32_t* misc) {
   const int t = threadIdx.x;
   uint32_t* blc = misc;        // [16] code-length counts
   uint32_t* first = misc + 16; // [16] first code per length
@@ -339,7 +340,7 @@ __device__ void huff_codes(ArrWork& w, const uint8_t* lens, uint32_t* wcnt, uint
   if (t < 48) misc[t] = 0;
   __syncthreads();
   uint32_t lmax = 0;
-  for (int s = t; s < kAlphabet; s += kHT) {
+  for (int s = t; s < nsym; s += kHT) {
     uint32_t l = lens[s];
     if (l) atomicAdd(&blc[l], 1u);
     lmax = max(lmax, l);
@@ -354,9 +355,9 @@ __device__ void huff_codes(ArrWork& w, const uint8_t* lens, uint32_t* wcnt, uint
   }
   lmax = block_max_u32(lmax, misc + 48);
   const uint64_t lt = lanemask_lt();
-  for (int slab = 0; slab * kHT < kAlphabet; slab++) {
+  for (int slab = 0; slab * kHT < nsym; slab++) {
     const int s = slab * kHT + t;
-    const uint32_t l = s < kAlphabet ? lens[s] : 0u;
+    const uint32_t l = s < nsym ? lens[s] : 0u;
     uint32_t rank = 0, urank = 0;
     for (uint32_t L = 1; L <= (uint32_t)kMaxLen; L++) {
       uint64_t m = __ballot(l == L);
@@ -369,7 +370,7 @@ __device__ void huff_codes(ArrWork& w, const uint8_t* lens, uint32_t* wcnt, uint
       if (lane_id() == 0) wcnt[wave_id() * 16 + 0] = (uint32_t)__popcll(m);
     }
     __syncthreads();
-    if (s < kAlphabet) {
+    if (s < nsym) {
       if (l) {
         uint32_t r = run[l] + rank, u = run[0] + urank;
         for (int j = 0; j < wave_id(); j++) {
@@ -397,7 +398,6 @@ __device__ void huff_codes(ArrWork& w, const uint8_t* lens, uint32_t* wcnt, uint
 }
 
 __device__ inline void empty_codes(ArrWork& w) {
-  for (int s = threadIdx.x; s < kAlphabet; s += kHT) w.lc[s] = 0;
   if (threadIdx.x == 0) {
     w.U = 0;
     w.L = 0;
@@ -438,19 +438,28 @@ __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* p
   for (int j = 0; j < kHT / kWave; j++) mx = smx[j] > mx ? smx[j] : mx;
   const uint64_t n = arr_len(e.in);
   const int top = n ? sym_bound(mx) : -1;
+  // only symbols up to the largest value's can occur; every loop below stops
+  // there (entries past it are never read)
+  const int nsym = top + 1;
   uint32_t cnt[kPer];
   uint32_t* src = part + (uint64_t)e.copy0 * kAlphabet;
 #pragma unroll
   for (int j = 0; j < kPer; j++) {
     const int s = t + kHT * j;
     uint32_t v = 0;
-    if (s <= top)
-      for (uint32_t c = 0; c < e.copies; c++) {
-        v += src[(uint64_t)c * kAlphabet + s];
-        src[(uint64_t)c * kAlphabet + s] = 0;
+    if (s < nsym) {
+      uint32_t x[kHistCopies];
+#pragma unroll
+      for (int c = 0; c < kHistCopies; c++)
+        x[c] = (uint32_t)c < e.copies ? src[(uint64_t)c * kAlphabet + s] : 0u;
+#pragma unroll
+      for (int c = 0; c < kHistCopies; c++) {
+        v += x[c];
+        if ((uint32_t)c < e.copies) src[(uint64_t)c * kAlphabet + s] = 0;
       }
+      w.hist[s] = v;
+    }
     cnt[j] = v;
-    if (s < kAlphabet) w.hist[s] = v;
   }
   if (t == 0) {
     w.maxv = mx;
@@ -462,10 +471,11 @@ __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* p
     if (t == 0) maxd[0] = 0;
     return;
   }
-  const uint32_t md = huff_build(cnt, smb, lens_all + (uint64_t)a * kHalvings * kAlphabet);
+  const uint32_t md = huff_build(cnt, nsym, smb, lens_all + (uint64_t)a * kHalvings * kAlphabet);
   if (t == 0) maxd[0] = md;
   if (md > (uint32_t)kMaxLen) return;
-  huff_codes(w, smb + kOffLens, reinterpret_cast<uint32_t*>(smb), reinterpret_cast<uint32_t*>(smb + kOffMisc));
+  huff_codes(w, nsym, smb + kOffLens, reinterpret_cast<uint32_t*>(smb),
+             reinterpret_cast<uint32_t*>(smb + kOffMisc));
 }
 
 // Fallback for arrays whose plain build is too deep (the oracle's loop halves
@@ -478,15 +488,16 @@ __global__ __launch_bounds__(kHT) void k_huff_lengths(const ArrWork* W, uint8_t*
   if (maxd_all[(uint64_t)a * kHalvings] <= (uint32_t)kMaxLen) return;
   const ArrWork& w = W[a];
   const int t = threadIdx.x;
+  const int nsym = sym_bound(w.maxv) + 1;
   uint32_t c[kPer];
 #pragma unroll
   for (int j = 0; j < kPer; j++) {
     int s = t + kHT * j;
-    uint32_t cc = s < kAlphabet ? w.hist[s] : 0u;
+    uint32_t cc = s < nsym ? w.hist[s] : 0u;
     for (int h = 0; h < halvings && cc > 1; h++) cc = (cc + 1u) >> 1;
     c[j] = cc;
   }
-  const uint32_t md = huff_build(c, reinterpret_cast<uint8_t*>(sm64),
+  const uint32_t md = huff_build(c, nsym, reinterpret_cast<uint8_t*>(sm64),
                                  lens_all + ((uint64_t)a * kHalvings + halvings) * kAlphabet);
   if (t == 0) maxd_all[(uint64_t)a * kHalvings + halvings] = md;
 }
@@ -506,9 +517,10 @@ __global__ __launch_bounds__(kHT) void k_huff_codes(ArrWork* W, const uint8_t* l
       hsel = h;
       break;
     }
+  const int nsym = sym_bound(w.maxv) + 1;
   const uint8_t* src = lens_all + ((uint64_t)a * kHalvings + hsel) * kAlphabet;
-  for (int s = threadIdx.x; s < kAlphabet; s += kHT) lens[s] = src[s];
-  huff_codes(w, lens, wcnt, misc);
+  for (int s = threadIdx.x; s < nsym; s += kHT) lens[s] = src[s];
+  huff_codes(w, nsym, lens, wcnt, misc);
 }
 
 // ------------------------------------------------------------------ chunk sizes
@@ -664,19 +676,35 @@ __global__ __launch_bounds__(kHT) void k_layout(ArrWork* W, EncRec* recs, int R,
     if (r < R) {
       EncRec& rc = recs[r];
       const int A = rc.h.A;
+      // every array's figures first (loads in flight together), then the choices
+      uint64_t n[kMaxArrays], mv[kMaxArrays], hw[kMaxArrays];
+      uint32_t U[kMaxArrays], nc[kMaxArrays];
+#pragma unroll
+      for (int a = 0; a < kMaxArrays; a++) {
+        if (a < A) {
+          const ArrWork& w = W[rc.a0 + a];
+          n[a] = w.n;
+          mv[a] = w.maxv;
+          U[a] = w.U;
+          nc[a] = w.nchunks;
+          hw[a] = w.huff_words;
+        }
+      }
       uint64_t off = (uint64_t)kHdrBytes + 8ull * rc.h.F + (uint64_t)kDirBytes * A;
-      for (int a = 0; a < A; a++) {
-        ArrWork& w = W[rc.a0 + a];
-        uint64_t n = w.n;
-        int wd = bitwidth64(w.maxv);
-        uint64_t fixed = 4 * ((n * (uint64_t)wd + 31) / 32);
-        uint64_t huff = 4ull * w.U + 4ull * w.nchunks + 4ull * w.huff_words;
-        bool use_h = w.U != 0 && huff < fixed;
-        w.coder = use_h ? 1u : 0u;
-        w.w = (uint32_t)wd;
-        w.nbytes = use_h ? huff : fixed;
-        w.off = off;
-        off += w.nbytes;
+#pragma unroll
+      for (int a = 0; a < kMaxArrays; a++) {
+        if (a < A) {
+          ArrWork& w = W[rc.a0 + a];
+          const int wd = bitwidth64(mv[a]);
+          const uint64_t fixed = 4 * ((n[a] * (uint64_t)wd + 31) / 32);
+          const uint64_t huff = 4ull * U[a] + 4ull * nc[a] + 4ull * hw[a];
+          const bool use_h = U[a] != 0 && huff < fixed;
+          w.coder = use_h ? 1u : 0u;
+          w.w = (uint32_t)wd;
+          w.nbytes = use_h ? huff : fixed;
+          w.off = off;
+          off += use_h ? huff : fixed;
+        }
       }
       size = off;
       rc.size = off;
