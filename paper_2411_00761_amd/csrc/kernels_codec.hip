@@ -146,6 +146,7 @@ __device__ inline uint32_t block_max_u32(uint32_t v, uint32_t* misc) {
 // by pointer jumping.  The lengths go to lens_g (global) and to LDS at
 // kOffLens; returns the longest code (block-uniform).
 constexpr int kPer = (kAlphabet + kHT - 1) / kHT;  // 5 symbols per thread
+constexpr int kHalvings = 32;  // counts < 2^31: after 31 halvings every count is 1
 
 __device__ uint32_t huff_build(const uint32_t* c, int nsym, uint8_t* smb, uint8_t* lens_g) {
   uint64_t* sm64 = reinterpret_cast<uint64_t*>(smb);
@@ -404,16 +405,157 @@ __device__ inline void empty_codes(ArrWork& w) {
   }
 }
 
-// One array per workgroup: sums its spread histogram copies (only the bins up
-// to the largest value's symbol can be non-zero) and clears them, builds the
-// code with no halving and, when its longest code fits kMaxLen bits, the
-// canonical codes.  maxd_all[a][0] tells the fallback launches whether they
-// are needed.
-constexpr int kHalvings = 32;  // counts < 2^31: after 31 halvings every count is 1
+// Code of an array whose symbols are all below 64 (temporal residuals, short
+// arrays), built by one wave without barriers: lane s holds symbol s's count;
+// the leaves are sorted by (count, symbol) with a lane bitonic sort, the
+// two-queue merge runs with wave-uniform indices over node values kept in
+// registers (readlane / writelane), depths are assigned in reverse creation
+// order, and the canonical codes come from a second lane sort by (length,
+// symbol).  Same lengths and codes as the workgroup build.  Counts are halved
+// (c -> ceil(c / 2)) until the longest code fits.  Writes lc, table, U, L.
+__device__ inline uint64_t lane_sort64(uint64_t key) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int size = 2; size <= kWave; size <<= 1) {
+#pragma unroll
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      const uint64_t x = shfl_xor_u64(key, stride);
+      const bool asc = (lane & size) == 0;
+      const bool lower = (lane & stride) == 0;
+      key = (lower == asc) ? (x < key ? x : key) : (x > key ? x : key);
+    }
+  }
+  return key;
+}
 
+__device__ inline uint32_t lane_u32(uint32_t v, uint32_t l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
+}
+
+__device__ void small_code(ArrWork& w, uint32_t count, uint32_t* maxd_out) {
+  const uint32_t lane = (uint32_t)lane_id();
+  const uint64_t used = __ballot(count != 0);
+  const uint32_t U = (uint32_t)__popcll(used);
+  uint32_t len = 0;  // of this lane's symbol
+  uint32_t md = 0;
+  if (U == 1) {
+    len = count ? 1u : 0u;
+    md = 1;
+  } else {
+    for (int h = 0; h < kHalvings; h++) {
+      uint32_t c = count;
+      for (int j = 0; j < h && c > 1; j++) c = (c + 1u) >> 1;
+      // leaves in (count, symbol) order; unused symbols sort last
+      const uint64_t key = lane_sort64(c ? (((uint64_t)c << 13) | lane) : ~0ull);
+      const uint32_t lw = (uint32_t)(key >> 13);   // leaf weight (lane i = leaf i)
+      const uint32_t ls = (uint32_t)(key & 0x1FFFu);
+      uint32_t iw = 0;     // internal node weights (lane k = internal node k)
+      uint32_t lpar = 0;   // parent of leaf i (a node id: internal k is U + k)
+      uint32_t ipar = 0;   // parent of internal node k
+      uint32_t li = 0, ii = 0;
+      constexpr uint32_t kInf = 0xFFFFFFFFu;
+      for (uint32_t nxt = 0; nxt + 1 < U; nxt++) {
+        const uint32_t L0 = li < U ? lane_u32(lw, li) : kInf;
+        const uint32_t L1 = li + 1 < U ? lane_u32(lw, li + 1) : kInf;
+        const uint32_t I0 = ii < nxt ? lane_u32(iw, ii) : kInf;
+        const uint32_t I1 = ii + 1 < nxt ? lane_u32(iw, ii + 1) : kInf;
+        uint32_t node0, node1, w0, w1, lh, ih;
+        if (L0 <= I0) {
+          node0 = li++;
+          w0 = L0;
+          lh = L1;
+          ih = I0;
+        } else {
+          node0 = U + ii++;
+          w0 = I0;
+          lh = L0;
+          ih = I1;
+        }
+        if (lh <= ih) {
+          node1 = li++;
+          w1 = lh;
+        } else {
+          node1 = U + ii++;
+          w1 = ih;
+        }
+        if (lane == nxt) iw = w0 + w1;
+        if (node0 < U) {
+          if (lane == node0) lpar = U + nxt;
+        } else if (lane == node0 - U) {
+          ipar = U + nxt;
+        }
+        if (node1 < U) {
+          if (lane == node1) lpar = U + nxt;
+        } else if (lane == node1 - U) {
+          ipar = U + nxt;
+        }
+      }
+      // depths: the root (internal U - 2) is 0; parents are created after
+      // their children
+      uint32_t idep = 0;
+      for (int k = (int)U - 3; k >= 0; k--) {
+        const uint32_t p = lane_u32(ipar, (uint32_t)k) - U;
+        const uint32_t d = lane_u32(idep, p) + 1;
+        if (lane == (uint32_t)k) idep = d;
+      }
+      // (every lane takes part in the shuffle; only leaves keep the result)
+      const uint32_t pd = (uint32_t)__shfl((int)idep, lane < U ? (int)(lpar - U) : 0, kWave);
+      const uint32_t ldep = lane < U ? pd + 1 : 0;
+      md = ldep;
+#pragma unroll
+      for (int d = kWave / 2; d > 0; d >>= 1) md = max(md, (uint32_t)__shfl_xor((int)md, d, kWave));
+      if (md <= (uint32_t)kMaxLen || h == kHalvings - 1) {
+        // lengths back to symbol lanes: leaf i carries symbol ls
+        const uint64_t k2 = lane_sort64(lane < U ? (((uint64_t)ls << 8) | ldep) : ~0ull);
+        const uint32_t s2 = (uint32_t)(k2 >> 8), d2 = (uint32_t)(k2 & 0xFFu);
+        // lane s now holds the s-th used symbol in ascending order
+        for (uint32_t u = 0; u < U; u++) {
+          const uint32_t su = lane_u32(s2, u), du = lane_u32(d2, u);
+          if (lane == su) len = du;
+        }
+        break;
+      }
+    }
+  }
+  // canonical codes: shorter first, ties by symbol
+  uint32_t first = 0, before = 0;
+  {
+    uint32_t code = 0;
+    for (uint32_t l = 1; l <= (uint32_t)kMaxLen; l++) {
+      const uint32_t prev = l > 1 ? (uint32_t)__popcll(__ballot(len == l - 1)) : 0u;
+      code = (code + prev) << 1;
+      if (len == l) first = code;
+    }
+  }
+  const uint64_t lt = lanemask_lt();
+  for (uint32_t l = 1; l <= (uint32_t)kMaxLen; l++) {
+    const uint64_t m = __ballot(len == l);
+    if (len == l) before = (uint32_t)__popcll(m & lt);
+  }
+  uint32_t lmax = len;
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) lmax = max(lmax, (uint32_t)__shfl_xor((int)lmax, d, kWave));
+  if (count) {
+    w.lc[lane] = (first + before) | (len << 16);
+    w.table[(uint32_t)__popcll(used & lt)] = lane | (len << 16);
+  }
+  if (lane == 0) {
+    w.U = U;
+    w.L = lmax;
+    *maxd_out = md;
+  }
+}
+
+// One array per workgroup: sums its spread histogram copies (only the bins up
+// to the largest value's symbol can be non-zero) and clears them, then builds
+// the code: by one wave when every symbol is below 64, else by the workgroup
+// with no halving, and with inline halvings when `inline_halve` is set (short
+// alphabets, as temporal residuals have).  maxd_all[a][0] tells the fallback
+// launches (candidate halvings side by side) whether they are needed.
 __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* part,
                                                     unsigned long long* part_max, ArrWork* W,
-                                                    uint8_t* lens_all, uint32_t* maxd_all) {
+                                                    uint8_t* lens_all, uint32_t* maxd_all,
+                                                    int inline_halve) {
   __shared__ uint64_t sm64[8192];
   __shared__ unsigned long long smx[kHT / kWave];
   uint8_t* smb = reinterpret_cast<uint8_t*>(sm64);
@@ -471,7 +613,16 @@ __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* p
     if (t == 0) maxd[0] = 0;
     return;
   }
-  const uint32_t md = huff_build(cnt, nsym, smb, lens_all + (uint64_t)a * kHalvings * kAlphabet);
+  if (nsym <= kWave) {
+    if (wave_id() == 0) small_code(w, cnt[0], maxd);
+    return;
+  }
+  uint32_t md = huff_build(cnt, nsym, smb, lens_all + (uint64_t)a * kHalvings * kAlphabet);
+  for (int h = 1; inline_halve && md > (uint32_t)kMaxLen && h < kHalvings; h++) {
+#pragma unroll
+    for (int j = 0; j < kPer; j++) cnt[j] = cnt[j] > 1 ? (cnt[j] + 1u) >> 1 : cnt[j];
+    md = huff_build(cnt, nsym, smb, lens_all + (uint64_t)a * kHalvings * kAlphabet);
+  }
   if (t == 0) maxd[0] = md;
   if (md > (uint32_t)kMaxLen) return;
   huff_codes(w, nsym, smb + kOffLens, reinterpret_cast<uint32_t*>(smb),
@@ -1217,9 +1368,14 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, uint32_t* 
               k_hist<<<L.hist_blocks, kThreads, 0, s>>>(L.arrs, pre_hist, NA, hist_part, hist_max));
   // the plain build (and its codes) per array; the halving candidates and their
   // codes only run for arrays whose plain build is too deep
-  k_huff_build<<<NA, kHT, 0, s>>>(L.arrs, hist_part, hist_max, work, huff_lens, huff_maxd);
-  k_huff_lengths<<<dim3(NA, kHalvings - 1), kHT, 0, s>>>(work, huff_lens, huff_maxd);
-  k_huff_codes<<<NA, kHT, 0, s>>>(work, huff_lens, huff_maxd);
+  // Temporal residual arrays (hist_done) halve inline: their alphabets are
+  // short and the fallback launches would cost more than they save.
+  k_huff_build<<<NA, kHT, 0, s>>>(L.arrs, hist_part, hist_max, work, huff_lens, huff_maxd,
+                                  hist_done ? 1 : 0);
+  if (!hist_done) {
+    k_huff_lengths<<<dim3(NA, kHalvings - 1), kHT, 0, s>>>(work, huff_lens, huff_maxd);
+    k_huff_codes<<<NA, kHT, 0, s>>>(work, huff_lens, huff_maxd);
+  }
   LCP_TIMED("chunk_bits", L.values * 4ull, s, {
     switch (chunk_log2) {
       case 9: k_chunk_bits<2><<<L.chunk_blocks, kThreads, 0, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, chunk_words); break;

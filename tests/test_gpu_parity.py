@@ -207,3 +207,31 @@ def test_batched_decompress_equals_per_frame(lcp):
         rec = out[offs[j]:offs[j + 1]].cpu().numpy().tobytes()
         w = ost.decompress(rec)
         assert all(bits_equal(batch[j][f].cpu().numpy(), w[f]) for f in range(3)), j
+
+
+def test_temporal_residuals_need_the_length_limit(lcp):
+    """Residual counts following the Fibonacci numbers make a Huffman tree 22
+    deep, so the 13-bit limit halves the counts; every residual symbol is
+    below 64, the alphabet the one-wave code builder handles."""
+    fib = [1, 1]
+    while len(fib) < 23:
+        fib.append(fib[-1] + fib[-2])
+    n = sum(fib)
+    rng = np.random.default_rng(77)
+    x0 = datagen.uniform_frame(n, hi=50.0, seed=78)
+    grids = O.grids_for(x0, O.EB_ABS, 1e-3)
+    r = np.repeat(np.arange(23, dtype=np.int64), fib)
+    x1 = np.empty_like(x0)
+    for f in range(3):
+        rr = rng.permutation(r) if f else r[rng.permutation(n)]
+        x1[f] = O.reconstruct(O.quantize(x0[f], grids[f]) + rr, grids[f])
+    ost = O.Stream(O.EB_ABS, 1e-3, batch_size=0, block_log2=6, max_n=n)
+    plan = lcp.Plan(1e-3, lcp.EB_ABS, multi_frame=True, batch_size=0, block_log2=6, max_particles=n)
+    for t, (x, m) in enumerate([(x0, O.METHOD_S), (x1, O.METHOD_T)]):
+        want, wused, _ = ost.compress(x, method=m)
+        out, offs, used, _ = plan.compress([torch.from_numpy(x).cuda()], methods=[m])
+        rec = out[offs[0]:offs[1]].cpu().numpy().tobytes()
+        assert used[0] == wused == m, t
+        assert rec == want, f"frame {t}: " + diff_report(rec, want)
+    P = fmt_ref.parse(want)
+    assert P["mode"] == 1 and any(d["coder"] == 1 for d in P["dirs"])
