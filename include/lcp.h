@@ -56,7 +56,7 @@ typedef enum {
   LCP_ERR_CORRUPT = 5,       /* a record failed validation while decoding */
   LCP_ERR_NO_REFERENCE = 6,  /* a temporal record's reference frame is not resident */
   LCP_ERR_BUDGET = 7,        /* the plan's scratch would exceed hbm_budget_bytes */
-  LCP_ERR_DEVICE = 8         /* a HIP runtime call failed */
+  LCP_ERR_DEVICE = 8         /* a HIP runtime call, or a device-side consistency check, failed */
 } lcp_status;
 
 enum { LCP_EB_ABS = 0, LCP_EB_REL_GLOBAL = 1, LCP_EB_REL_PER_FIELD = 2 };

@@ -329,10 +329,10 @@ __device__ uint32_t huff_build(const uint32_t* c, int nsym, uint8_t* smb, uint8_
 }
 
 // Canonical codes from code lengths in LDS: shorter first, ties by symbol
-// (RFC 1951 order), and the table of used symbols.  wcnt: kHT / kWave * 16
-// u32 and misc: 64 u32 of LDS scratch.
-__device__ void huff_codes(ArrWork& w, int nsym, const uint8_t* lens, uint32_t* wcnt,
-                           uint32_t* misc) {
+// (RFC 1951 order), and the table of used symbols; returns the number of used
+// symbols.  wcnt: kHT / kWave * 16 u32 and misc: 64 u32 of LDS scratch.
+__device__ uint32_t huff_codes(ArrWork& w, int nsym, const uint8_t* lens, uint32_t* wcnt,
+                               uint32_t* misc) {
   const int t = threadIdx.x;
   uint32_t* blc = misc;        // [16] code-length counts
   uint32_t* first = misc + 16; // [16] first code per length
@@ -392,10 +392,12 @@ __device__ void huff_codes(ArrWork& w, int nsym, const uint8_t* lens, uint32_t* 
     }
     __syncthreads();
   }
+  const uint32_t U = run[0];
   if (t == 0) {
-    w.U = run[0];
+    w.U = U;
     w.L = lmax;
   }
+  return U;
 }
 
 __device__ inline void empty_codes(ArrWork& w) {
@@ -412,7 +414,8 @@ __device__ inline void empty_codes(ArrWork& w) {
 // registers (readlane / writelane), depths are assigned in reverse creation
 // order, and the canonical codes come from a second lane sort by (length,
 // symbol).  Same lengths and codes as the workgroup build.  Counts are halved
-// (c -> ceil(c / 2)) until the longest code fits.  Writes lc, table, U, L.
+// (c -> ceil(c / 2)) until the longest code fits.  Writes lc, table, U, L;
+// returns this lane's symbol's code length.
 __device__ inline uint64_t lane_sort64(uint64_t key) {
   const int lane = lane_id();
 #pragma unroll
@@ -432,7 +435,7 @@ __device__ inline uint32_t lane_u32(uint32_t v, uint32_t l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
 }
 
-__device__ void small_code(ArrWork& w, uint32_t count, uint32_t* maxd_out) {
+__device__ uint32_t small_code(ArrWork& w, uint32_t count, uint32_t* maxd_out) {
   const uint32_t lane = (uint32_t)lane_id();
   const uint64_t used = __ballot(count != 0);
   const uint32_t U = (uint32_t)__popcll(used);
@@ -544,6 +547,54 @@ __device__ void small_code(ArrWork& w, uint32_t count, uint32_t* maxd_out) {
     w.L = lmax;
     *maxd_out = md;
   }
+  return len;
+}
+
+// ------------------------------------------------------------------ Huffman size
+// After the code is built: the exact code + raw bits of all the array's
+// symbols (chunk padding aside) bound the Huffman coding from below.  When that
+// bound is not below the fixed-length size, fixed length wins and the array is
+// never packed as Huffman; otherwise it is a candidate, packed with its word
+// total starting from zero.
+__device__ inline int extra_bits(int s) { return s >= kDirect ? s - kDirect + kFirstClassBits - 1 : 0; }
+
+__device__ inline uint32_t huff_candidate(uint32_t U, uint64_t n, uint64_t maxv,
+                                          unsigned long long bits, int chunk_log2) {
+  const uint64_t nchunks = (n + (1ull << chunk_log2) - 1) >> chunk_log2;
+  const uint64_t lower = 4ull * U + 4ull * nchunks + 4ull * ((bits + 31) / 32);
+  const uint64_t fixed = 4ull * ((n * (uint64_t)bitwidth64(maxv) + 31) / 32);
+  return (U != 0 && lower < fixed) ? 1u : 0u;
+}
+
+// All kHT threads: `part` is this thread's share of the bits; U the number of
+// used symbols, n and maxv the array's length and largest value.
+__device__ void finish_block(ArrWork& w, unsigned long long part, uint32_t U, uint64_t n,
+                             uint64_t maxv, int chunk_log2, unsigned long long* red) {
+  __syncthreads();
+  if (threadIdx.x == 0) red[0] = 0;
+  __syncthreads();
+  atomicAdd(red, part);
+  __syncthreads();
+  const unsigned long long bits = red[0];
+  if (threadIdx.x == 0) {
+    w.huff_bits = bits;
+    w.cand = huff_candidate(U, n, maxv, bits, chunk_log2);
+    w.nchunks = (uint32_t)((n + (1ull << chunk_log2) - 1) >> chunk_log2);
+    w.huff_words = 0;
+  }
+}
+
+// One wave (the small-alphabet path): `part` is this lane's share.
+__device__ void finish_wave(ArrWork& w, unsigned long long part, uint32_t U, uint64_t n,
+                            uint64_t maxv, int chunk_log2) {
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) part += shfl_xor_u64(part, d);
+  if (lane_id() == 0) {
+    w.huff_bits = part;
+    w.cand = huff_candidate(U, n, maxv, part, chunk_log2);
+    w.nchunks = (uint32_t)((n + (1ull << chunk_log2) - 1) >> chunk_log2);
+    w.huff_words = 0;
+  }
 }
 
 // One array per workgroup: sums its spread histogram copies (only the bins up
@@ -555,9 +606,10 @@ __device__ void small_code(ArrWork& w, uint32_t count, uint32_t* maxd_out) {
 __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* part,
                                                     unsigned long long* part_max, ArrWork* W,
                                                     uint8_t* lens_all, uint32_t* maxd_all,
-                                                    int inline_halve) {
+                                                    int inline_halve, int chunk_log2) {
   __shared__ uint64_t sm64[8192];
   __shared__ unsigned long long smx[kHT / kWave];
+  __shared__ unsigned long long red[1];
   uint8_t* smb = reinterpret_cast<uint8_t*>(sm64);
   const int a = blockIdx.x, t = threadIdx.x;
   const EncArr& e = E[a];
@@ -610,13 +662,23 @@ __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* p
   uint32_t* maxd = maxd_all + (uint64_t)a * kHalvings;
   if (n == 0) {
     empty_codes(w);
-    if (t == 0) maxd[0] = 0;
+    if (t == 0) {
+      maxd[0] = 0;
+      w.cand = 0;
+    }
     return;
   }
   if (nsym <= kWave) {
-    if (wave_id() == 0) small_code(w, cnt[0], maxd);
+    if (wave_id() == 0) {
+      const uint32_t len = small_code(w, cnt[0], maxd);
+      const uint32_t U = (uint32_t)__popcll(__ballot(cnt[0] != 0));
+      finish_wave(w, (unsigned long long)cnt[0] * len, U, n, mx, chunk_log2);
+    }
     return;
   }
+  uint32_t orig[kPer];
+#pragma unroll
+  for (int j = 0; j < kPer; j++) orig[j] = cnt[j];
   uint32_t md = huff_build(cnt, nsym, smb, lens_all + (uint64_t)a * kHalvings * kAlphabet);
   for (int h = 1; inline_halve && md > (uint32_t)kMaxLen && h < kHalvings; h++) {
 #pragma unroll
@@ -625,8 +687,16 @@ __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* p
   }
   if (t == 0) maxd[0] = md;
   if (md > (uint32_t)kMaxLen) return;
-  huff_codes(w, nsym, smb + kOffLens, reinterpret_cast<uint32_t*>(smb),
-             reinterpret_cast<uint32_t*>(smb + kOffMisc));
+  const uint32_t U = huff_codes(w, nsym, smb + kOffLens, reinterpret_cast<uint32_t*>(smb),
+                                reinterpret_cast<uint32_t*>(smb + kOffMisc));
+  unsigned long long part_bits = 0;
+  const uint8_t* lens_l = smb + kOffLens;
+#pragma unroll
+  for (int j = 0; j < kPer; j++) {
+    const int s = t + kHT * j;
+    if (s < nsym) part_bits += (unsigned long long)orig[j] * (lens_l[s] + extra_bits(s));
+  }
+  finish_block(w, part_bits, U, n, mx, chunk_log2, red);
 }
 
 // Fallback for arrays whose plain build is too deep (the oracle's loop halves
@@ -654,11 +724,13 @@ __global__ __launch_bounds__(kHT) void k_huff_lengths(const ArrWork* W, uint8_t*
 }
 
 // Fallback codes: the fewest halvings whose longest code fits (31 always fit).
-__global__ __launch_bounds__(kHT) void k_huff_codes(ArrWork* W, const uint8_t* lens_all,
-                                                    const uint32_t* maxd_all) {
+__global__ __launch_bounds__(kHT) void k_huff_codes(const EncArr* E, ArrWork* W,
+                                                    const uint8_t* lens_all,
+                                                    const uint32_t* maxd_all, int chunk_log2) {
   __shared__ uint8_t lens[kAlphabet];
   __shared__ uint32_t wcnt[kHT / kWave * 16];
   __shared__ uint32_t misc[64];
+  __shared__ unsigned long long red[1];
   const int a = blockIdx.x;
   if (maxd_all[(uint64_t)a * kHalvings] <= (uint32_t)kMaxLen) return;
   ArrWork& w = W[a];
@@ -671,7 +743,11 @@ __global__ __launch_bounds__(kHT) void k_huff_codes(ArrWork* W, const uint8_t* l
   const int nsym = sym_bound(w.maxv) + 1;
   const uint8_t* src = lens_all + ((uint64_t)a * kHalvings + hsel) * kAlphabet;
   for (int s = threadIdx.x; s < nsym; s += kHT) lens[s] = src[s];
-  huff_codes(w, nsym, lens, wcnt, misc);
+  const uint32_t U = huff_codes(w, nsym, lens, wcnt, misc);
+  unsigned long long part_bits = 0;
+  for (int s = threadIdx.x; s < nsym; s += kHT)
+    part_bits += (unsigned long long)w.hist[s] * (lens[s] + extra_bits(s));
+  finish_block(w, part_bits, U, w.n, w.maxv, chunk_log2, red);
 }
 
 // ------------------------------------------------------------------ chunk sizes
@@ -704,74 +780,6 @@ __device__ inline uint32_t run_bits(const ArrIn& in, const ArrWork& w, const uin
   return bits;
 }
 
-template <int RUN>
-__global__ __launch_bounds__(kThreads) void k_chunk_bits(const EncArr* E, const ArrWork* W,
-                                                         const uint32_t* pre, int NA,
-                                                         int chunk_log2, uint32_t* cw) {
-  __shared__ uint32_t sm[kThreads / kWave];
-  __shared__ uint32_t lc_lds[kPrivBins];
-  const uint32_t a = array_of_block(pre, NA, blockIdx.x);
-  const uint32_t lb = blockIdx.x - pre[a], nb = pre[a + 1] - pre[a];
-  const ArrIn in = E[a].in;
-  const ArrWork& w = W[a];
-  const uint64_t n = w.n;
-  const uint64_t C = 1ull << chunk_log2;
-  const uint64_t nchunks = (n + C - 1) >> chunk_log2;
-  if (w.U == 0 || lb >= nchunks) return;
-  load_codes(w, lc_lds);
-  __syncthreads();
-  uint32_t* cwa = cw + E[a].cw0;
-  const uint64_t run = C >= (uint64_t)kThreads ? C / kThreads : 1;
-  for (uint64_t c = lb; c < nchunks; c += nb) {
-    const uint64_t cend = min(n, (c + 1) * C);
-    const uint64_t i0 = min(cend, c * C + threadIdx.x * run);
-    const uint64_t i1 = min(cend, i0 + run);
-    uint64_t vals[RUN];
-    uint32_t bits = wave_sum(run_bits<RUN>(in, w, lc_lds, i0, i1, vals));
-    if (lane_id() == 0) sm[wave_id()] = bits;
-    __syncthreads();
-    if (threadIdx.x == 0) cwa[c] = (sm[0] + sm[1] + sm[2] + sm[3] + 31u) >> 5;
-    __syncthreads();
-  }
-}
-
-// Inclusive scan of one array's chunk word counts (one workgroup per array).
-__global__ __launch_bounds__(kHT) void k_chunk_scan(const EncArr* E, ArrWork* W, int chunk_log2,
-                                                    uint32_t* cw) {
-  __shared__ uint32_t sm[kHT / kWave + 1];
-  const int a = blockIdx.x;
-  ArrWork& w = W[a];
-  const uint64_t n = w.n;
-  const uint64_t nchunks = (n + (1ull << chunk_log2) - 1) >> chunk_log2;
-  uint32_t* p = cw + E[a].cw0;
-  uint64_t carry = 0;
-  if (w.U != 0) {
-    for (uint64_t base = 0; base < nchunks; base += (uint64_t)kHT * 4) {
-      uint32_t v[4], loc = 0;
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        uint64_t i = base + (uint64_t)threadIdx.x * 4 + j;
-        v[j] = i < nchunks ? p[i] : 0u;
-        loc += v[j];
-      }
-      uint32_t tot;
-      uint32_t inc = block_incl_scan(loc, sm, &tot);
-      uint64_t r = carry + inc - loc;
-#pragma unroll
-      for (int j = 0; j < 4; j++) {
-        uint64_t i = base + (uint64_t)threadIdx.x * 4 + j;
-        r += v[j];
-        if (i < nchunks) p[i] = (uint32_t)r;
-      }
-      carry += tot;
-    }
-  }
-  if (threadIdx.x == 0) {
-    w.nchunks = (uint32_t)nchunks;
-    w.huff_words = carry;
-  }
-}
-
 // ------------------------------------------------------------------ layout
 __device__ inline void put32(uint8_t* base, uint64_t off, uint32_t v) {
   *reinterpret_cast<uint32_t*>(base + off) = v;
@@ -782,37 +790,35 @@ __device__ inline void put64(uint8_t* base, uint64_t off, uint64_t v) {
 }
 
 // Chooses each array's coder (the shorter; a tie keeps fixed length), places
-// the arrays, sizes the records and places them back to back (one thread per
-// record, workgroup scan of the sizes), then writes headers, grids and
-// directories.  Every record size is a multiple of 4 bytes.
-__device__ inline void write_header(const EncRec& rc, const ArrWork* W, uint8_t* out) {
-  const RecHdr& h = rc.h;
-  const int A = h.A;
-  const uint64_t hdr = (uint64_t)kHdrBytes + 8ull * h.F + (uint64_t)kDirBytes * A;
-  for (uint64_t o = 0; o < hdr; o += 4) put32(out, o, 0u);
+// the arrays, sizes the records and places them back to back, then writes
+// each header, grid and directory that fits in the output.  Records are taken
+// kLayRecs at a time: thread j < kLayRecs reads record j's header, thread
+// (j, a) = (t / kMaxArrays, t % kMaxArrays) reads and decides array a of
+// record j, record threads turn the array sizes into offsets, and a workgroup
+// scan of the record sizes places the records.  Each phase is one round of
+// independent loads.  Every record size is a multiple of 4 bytes.
+constexpr int kLayRecs = kHT / kMaxArrays;
+
+__device__ inline void write_header(const RecHdr& h, uint64_t B, uint64_t size, uint8_t* out) {
+  const uint64_t hdr = (uint64_t)kHdrBytes + 8ull * h.F + (uint64_t)kDirBytes * h.A;
   put32(out, 0, kMagic);
   put32(out, 4, (uint32_t)kVersion | ((uint32_t)h.mode << 16) | ((uint32_t)h.F << 24));
-  put32(out, 8, (uint32_t)h.k | ((uint32_t)h.chunk_log2 << 8) | ((uint32_t)A << 16));
+  put32(out, 8, (uint32_t)h.k | ((uint32_t)h.chunk_log2 << 8) | ((uint32_t)h.A << 16));
   put32(out, 12, (uint32_t)hdr);
   put64(out, 16, h.n);
-  put64(out, 24, h.mode == 0 ? (uint64_t)*rc.B_dev : 0ull);
-  put64(out, 32, rc.size);
+  put64(out, 24, B);
+  put64(out, 32, size);
   for (int d = 0; d < 3; d++) put32(out, 40 + 4 * d, h.bn[d]);
+  put32(out, 52, 0u);  // reserved words
   put64(out, 56, h.seq);
   put64(out, 64, h.ref_seq);
-  for (int f = 0; f < h.F; f++) {
-    put32(out, kHdrBytes + 8 * f, __float_as_uint(h.m[f]));
-    put32(out, kHdrBytes + 8 * f + 4, __float_as_uint(h.eb_q[f]));
-  }
-  for (int a = 0; a < A; a++) {
-    const ArrWork& w = W[rc.a0 + a];
-    uint64_t d = (uint64_t)kHdrBytes + 8ull * h.F + (uint64_t)kDirBytes * a;
-    uint32_t param = w.coder ? w.L : w.w;
-    put32(out, d, w.coder | (param << 8));
-    put32(out, d + 4, w.coder ? w.U : 0u);
-    put64(out, d + 8, w.n);
-    put64(out, d + 16, w.off);
-    put64(out, d + 24, w.nbytes);
+  put64(out, 72, 0ull);
+#pragma unroll
+  for (int f = 0; f < kMaxF; f++) {
+    if (f < h.F) {
+      put32(out, kHdrBytes + 8 * f, __float_as_uint(h.m[f]));
+      put32(out, kHdrBytes + 8 * f + 4, __float_as_uint(h.eb_q[f]));
+    }
   }
 }
 
@@ -820,60 +826,92 @@ __global__ __launch_bounds__(kHT) void k_layout(ArrWork* W, EncRec* recs, int R,
                                                 uint64_t cap, unsigned long long* offs,
                                                 uint32_t* err) {
   __shared__ unsigned long long sm[kHT / kWave + 1];
+  __shared__ uint32_t s_a0[kLayRecs];
+  __shared__ int s_A[kLayRecs], s_F[kLayRecs];
+  __shared__ unsigned long long s_nb[kLayRecs][kMaxArrays];  // bytes, then offsets
+  __shared__ unsigned long long s_roff[kLayRecs], s_size[kLayRecs];
+  const int t = (int)threadIdx.x;
+  const int j = t / kMaxArrays, a = t % kMaxArrays;
   unsigned long long carry = 0;
-  for (int base = 0; base < R; base += kHT) {
-    const int r = base + (int)threadIdx.x;
+  for (int base = 0; base < R; base += kLayRecs) {
+    const int r = base + t;
+    const bool hv = t < kLayRecs && r < R;
+    RecHdr h;
+    uint64_t B = 0;
+    if (hv) {
+      const EncRec& rc = recs[r];
+      h = rc.h;
+      s_a0[t] = rc.a0;
+      s_A[t] = h.A;
+      s_F[t] = h.F;
+      if (h.mode == 0) B = *rc.B_dev;
+    }
+    __syncthreads();
+    const bool av = j < kLayRecs && base + j < R && a < s_A[j];
+    uint32_t coder = 0, param = 0, U = 0;
+    uint64_t n = 0, nbytes = 0;
+    if (av) {
+      ArrWork& w = W[s_a0[j] + a];
+      n = w.n;
+      const uint64_t mv = w.maxv;
+      const uint32_t L = w.L, cand = w.cand, nc = w.nchunks;
+      const uint64_t hw = w.huff_words;
+      U = w.U;
+      const int wd = bitwidth64(mv);
+      const uint64_t fixed = 4 * ((n * (uint64_t)wd + 31) / 32);
+      const uint64_t huff = 4ull * U + 4ull * nc + 4ull * hw;
+      const bool use_h = cand && huff < fixed;
+      coder = use_h ? 1u : 0u;
+      param = use_h ? L : (uint32_t)wd;
+      if (!use_h) U = 0;
+      nbytes = use_h ? huff : fixed;
+      w.coder = coder;
+      w.w = (uint32_t)wd;
+      w.nbytes = nbytes;
+      s_nb[j][a] = nbytes;
+    }
+    __syncthreads();
     unsigned long long size = 0;
-    if (r < R) {
-      EncRec& rc = recs[r];
-      const int A = rc.h.A;
-      // every array's figures first (loads in flight together), then the choices
-      uint64_t n[kMaxArrays], mv[kMaxArrays], hw[kMaxArrays];
-      uint32_t U[kMaxArrays], nc[kMaxArrays];
-#pragma unroll
-      for (int a = 0; a < kMaxArrays; a++) {
-        if (a < A) {
-          const ArrWork& w = W[rc.a0 + a];
-          n[a] = w.n;
-          mv[a] = w.maxv;
-          U[a] = w.U;
-          nc[a] = w.nchunks;
-          hw[a] = w.huff_words;
-        }
-      }
-      uint64_t off = (uint64_t)kHdrBytes + 8ull * rc.h.F + (uint64_t)kDirBytes * A;
-#pragma unroll
-      for (int a = 0; a < kMaxArrays; a++) {
-        if (a < A) {
-          ArrWork& w = W[rc.a0 + a];
-          const int wd = bitwidth64(mv[a]);
-          const uint64_t fixed = 4 * ((n[a] * (uint64_t)wd + 31) / 32);
-          const uint64_t huff = 4ull * U[a] + 4ull * nc[a] + 4ull * hw[a];
-          const bool use_h = U[a] != 0 && huff < fixed;
-          w.coder = use_h ? 1u : 0u;
-          w.w = (uint32_t)wd;
-          w.nbytes = use_h ? huff : fixed;
-          w.off = off;
-          off += use_h ? huff : fixed;
-        }
+    if (hv) {
+      uint64_t off = (uint64_t)kHdrBytes + 8ull * h.F + (uint64_t)kDirBytes * h.A;
+      for (int q = 0; q < h.A; q++) {
+        const unsigned long long bq = s_nb[t][q];
+        s_nb[t][q] = off;
+        off += bq;
       }
       size = off;
-      rc.size = off;
     }
     unsigned long long tot;
     const unsigned long long incl = block_incl_scan(size, sm, &tot);
-    if (r < R) {
-      recs[r].off = carry + incl - size;
-      offs[r] = carry + incl - size;
+    if (hv) {
+      const unsigned long long roff = carry + incl - size;
+      s_roff[t] = roff;
+      s_size[t] = size;
+      recs[r].size = size;
+      recs[r].off = roff;
+      offs[r] = roff;
+      if (roff + size <= cap) write_header(h, B, size, out + roff);
+    }
+    __syncthreads();
+    if (av) {
+      const uint64_t aoff = s_nb[j][a];
+      W[s_a0[j] + a].off = aoff;
+      const unsigned long long roff = s_roff[j];
+      if (roff + s_size[j] <= cap) {
+        uint8_t* o = out + roff;
+        const uint64_t d = (uint64_t)kHdrBytes + 8ull * s_F[j] + (uint64_t)kDirBytes * a;
+        put32(o, d, coder | (param << 8));
+        put32(o, d + 4, U);
+        put64(o, d + 8, n);
+        put64(o, d + 16, aoff);
+        put64(o, d + 24, nbytes);
+      }
     }
     carry += tot;
+    __syncthreads();
   }
-  if (threadIdx.x == 0) offs[R] = carry;
-  if (carry > cap) {
-    if (threadIdx.x == 0) atomicOr(err, kErrCapacity);
-    return;
-  }
-  for (int r = threadIdx.x; r < R; r += kHT) write_header(recs[r], W, out + recs[r].off);
+  if (t == 0) offs[R] = carry;
+  if (carry > cap && t == 0) atomicOr(err, kErrCapacity);
 }
 
 // ------------------------------------------------------------------ packing
@@ -934,72 +972,156 @@ struct BitSink {
   }
 };
 
-// One workgroup per chunk; thread t packs the t-th run of C/256 consecutive
-// symbols, starting at the bit offset given by a block prefix scan of the runs'
-// lengths, into the chunk's image in LDS, which is then written out coalesced.
+// Chunks of a Huffman candidate are independent: thread t packs the t-th run
+// of C/256 consecutive symbols at the bit offset given by a workgroup scan of
+// the runs' lengths into the chunk's image in LDS, which goes to the chunk's
+// own slot of the array's staging area (a slot holds C symbols of the longest
+// code and the most extra bits, enc_slot_words).  The chunk's word count goes
+// to cnt[c] and, summed per workgroup, into the array's total; where each
+// chunk lands in the record is settled by the copy once all are packed, so no
+// workgroup waits on another.
 template <int RUN>
-__global__ __launch_bounds__(kThreads) void k_pack_huff(const EncArr* E, const ArrWork* W,
-                                                        const EncRec* recs, const uint32_t* pre,
-                                                        int NA, int chunk_log2, const uint32_t* cw,
-                                                        uint32_t max_words, uint8_t* out,
-                                                        const uint32_t* err) {
+__global__ __launch_bounds__(kThreads) void k_pack_huff(const EncArr* E, ArrWork* W,
+                                                        const uint32_t* pre, int NA,
+                                                        int chunk_log2, uint32_t* cnt,
+                                                        uint32_t* stage, uint32_t slot32,
+                                                        uint32_t slot64, uint32_t* err) {
   extern __shared__ uint32_t buf[];
   __shared__ uint32_t sm[kThreads / kWave + 1];
   __shared__ uint32_t lc_lds[kPrivBins];
   const uint32_t a = array_of_block(pre, NA, blockIdx.x);
   const uint32_t lb = blockIdx.x - pre[a], nb = pre[a + 1] - pre[a];
-  const ArrWork& w = W[a];
-  if (w.coder != 1 || (*err & kErrCapacity)) return;
+  ArrWork& w = W[a];
+  if (!w.cand) return;
   load_codes(w, lc_lds);
   __syncthreads();
-  const ArrIn in = E[a].in;
-  const uint64_t n = w.n, nchunks = w.nchunks, U = w.U;
-  uint32_t* tab = reinterpret_cast<uint32_t*>(out + recs[E[a].rec].off + w.off);
-  uint32_t* offs = tab + U;
-  uint32_t* payload = offs + nchunks;
-  const uint32_t* ce = cw + E[a].cw0;
-  const uint64_t gid = (uint64_t)lb * blockDim.x + threadIdx.x;
-  const uint64_t gstride = (uint64_t)nb * blockDim.x;
-  for (uint64_t j = gid; j < U; j += gstride) tab[j] = w.table[j];
-  for (uint64_t c = gid; c < nchunks; c += gstride) offs[c] = ce[c];
+  const EncArr& e = E[a];
+  const ArrIn in = e.in;
+  const uint64_t n = w.n;
   const uint64_t C = 1ull << chunk_log2;
+  const uint32_t nchunks = (uint32_t)((n + C - 1) >> chunk_log2);
+  const uint32_t slot = in.is64 ? slot64 : slot32;
+  uint32_t* cnta = cnt + e.cw0;
+  uint32_t* pay = stage + e.stage0;
   const uint64_t run = C >= (uint64_t)kThreads ? C / kThreads : 1;
-  for (uint64_t c = lb; c < nchunks; c += nb) {
-    const uint32_t wbeg = c ? ce[c - 1] : 0u;
-    const uint32_t nw = ce[c] - wbeg;
-    const bool fits = nw <= max_words;
-    for (uint32_t j = threadIdx.x; j < nw && fits; j += kThreads) buf[j] = 0;
-    const uint64_t cend = min(n, (c + 1) * C);
-    const uint64_t i0 = min(cend, c * C + threadIdx.x * run);
+  unsigned long long words = 0;  // thread 0: this workgroup's share of the array
+  for (uint32_t c = lb; c < nchunks; c += nb) {
+    const uint64_t cend = min(n, (uint64_t)(c + 1) * C);
+    const uint64_t i0 = min(cend, (uint64_t)c * C + threadIdx.x * run);
     const uint64_t i1 = min(cend, i0 + run);
     uint64_t vals[RUN];
     const uint32_t bits = run_bits<RUN>(in, w, lc_lds, i0, i1, vals);
     uint32_t total;
     const uint32_t start = block_incl_scan(bits, sm, &total) - bits;
+    const uint32_t nw = (total + 31u) >> 5;
+    // a chunk beyond its slot would mean the code and the data disagree:
+    // flagged, never written
+    const bool fits = nw <= slot;
+    if (threadIdx.x == 0) {
+      if (!fits) atomicOr(err, kErrCorrupt);
+      cnta[c] = nw;
+      words += nw;
+    }
+    for (uint32_t j = threadIdx.x; j < nw && fits; j += kThreads) buf[j] = 0;
+    __syncthreads();
     if (bits && fits) {
       BitSink sk{0ull, (int)(start & 31u), start >> 5, buf};
 #pragma unroll
       for (int j = 0; j < RUN; j++) {
         if (i0 + j >= i1) break;
         const uint64_t v = vals[j];
-        int e;
-        const int sym = symbol_of(v, &e);
+        int ex;
+        const int sym = symbol_of(v, &ex);
         const uint32_t lc = code_of(w, lc_lds, sym);
         sk.push(lc & 0xFFFFu, (int)(lc >> 16));
-        if (e) {
-          const uint64_t x = v - (1ull << e);
-          if (e > 32) {
-            sk.push(x >> 32, e - 32);
+        if (ex) {
+          const uint64_t x = v - (1ull << ex);
+          if (ex > 32) {
+            sk.push(x >> 32, ex - 32);
             sk.push(x & 0xFFFFFFFFull, 32);
           } else {
-            sk.push(x, e);
+            sk.push(x, ex);
           }
         }
       }
       sk.flush();
     }
     __syncthreads();
-    for (uint32_t j = threadIdx.x; j < nw && fits; j += kThreads) payload[wbeg + j] = buf[j];
+    uint32_t* dst = pay + (uint64_t)c * slot;
+    for (uint32_t j = threadIdx.x; j < nw && fits; j += kThreads) dst[j] = buf[j];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && words) atomicAdd(&w.huff_words, words);
+}
+
+// Huffman arrays the layout kept: code table, chunk end offsets and the
+// payload gathered from the chunks' slots into the record.  Workgroup lb of
+// the array's nb handles a contiguous range of chunks: it sums the word counts
+// before its range (eight loads in flight per thread), then takes the range
+// 256 chunks at a time, scanning their counts and copying their words as one
+// flat range (a word finds its chunk by binary search over the tile's
+// offsets), so that loads of different chunks overlap.
+__global__ __launch_bounds__(kThreads) void k_copy_huff(const EncArr* E, const ArrWork* W,
+                                                        const EncRec* recs, const uint32_t* pre,
+                                                        int NA, const uint32_t* cnt,
+                                                        const uint32_t* stage, uint32_t slot32,
+                                                        uint32_t slot64, uint8_t* out,
+                                                        const uint32_t* err) {
+  __shared__ unsigned long long sm[kThreads / kWave + 1];
+  __shared__ uint32_t c_end[kThreads];  // inclusive word ends inside the tile
+  const uint32_t a = array_of_block(pre, NA, blockIdx.x);
+  const uint32_t lb = blockIdx.x - pre[a], nb = pre[a + 1] - pre[a];
+  const ArrWork& w = W[a];
+  if (w.coder != 1 || (*err & (kErrCapacity | kErrCorrupt))) return;
+  const EncArr& e = E[a];
+  const uint32_t U = w.U, nchunks = w.nchunks;
+  const uint32_t slot = e.in.is64 ? slot64 : slot32;
+  uint32_t* dst = reinterpret_cast<uint32_t*>(out + recs[e.rec].off + w.off);
+  uint32_t* dpay = dst + U + nchunks;
+  const uint32_t* cnta = cnt + e.cw0;
+  const uint32_t* pay = stage + e.stage0;
+  if (lb == 0)
+    for (uint32_t j = threadIdx.x; j < U; j += kThreads) dst[j] = w.table[j];
+  const uint32_t per = (nchunks + nb - 1) / nb;
+  const uint32_t c0 = min(nchunks, lb * per), c1 = min(nchunks, c0 + per);
+  if (c0 >= c1) return;
+  constexpr int kPf = 8;
+  unsigned long long part = 0;
+  for (uint32_t j0 = 0; j0 < c0; j0 += kThreads * kPf) {
+    uint32_t v[kPf];
+#pragma unroll
+    for (int q = 0; q < kPf; q++) {
+      const uint32_t j = j0 + q * kThreads + threadIdx.x;
+      v[q] = j < c0 ? cnta[j] : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < kPf; q++) part += v[q];
+  }
+  unsigned long long base;
+  block_incl_scan(part, sm, &base);
+  for (uint32_t t0 = c0; t0 < c1; t0 += kThreads) {
+    const uint32_t c = t0 + threadIdx.x;
+    const uint32_t m = min((uint32_t)kThreads, c1 - t0);
+    const unsigned long long k = c < c1 ? cnta[c] : 0u;
+    unsigned long long tot;
+    const unsigned long long incl = block_incl_scan(k, sm, &tot);
+    if (c < c1) {
+      dst[U + c] = (uint32_t)(base + incl);
+      c_end[threadIdx.x] = (uint32_t)incl;
+    }
+    __syncthreads();
+    uint32_t* d = dpay + base;
+    for (uint32_t j = threadIdx.x; j < (uint32_t)tot; j += kThreads) {
+      uint32_t lo = 0, hi = m - 1;  // first chunk of the tile ending after word j
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (c_end[mid] > j) hi = mid;
+        else lo = mid + 1;
+      }
+      const uint32_t start = lo ? c_end[lo - 1] : 0u;
+      d[j] = pay[(uint64_t)(t0 + lo) * slot + (j - start)];
+    }
+    base += tot;
     __syncthreads();
   }
 }
@@ -1351,60 +1473,64 @@ uint32_t enc_hist_copies(uint64_t n) {
   return c > (uint32_t)kHistCopies ? (uint32_t)kHistCopies : c;
 }
 uint32_t enc_chunk_blocks(uint64_t n, int chunk_log2) {
-  return gclamp((n + (1ull << chunk_log2) - 1) >> chunk_log2, 1024);
+  return gclamp((n + (1ull << chunk_log2) - 1) >> chunk_log2, 512);
+}
+uint32_t enc_copy_blocks(uint64_t n, int chunk_log2) {
+  return gclamp((n + (1ull << chunk_log2) - 1) >> chunk_log2, 256);
 }
 uint32_t enc_fixed_blocks(uint64_t n) { return gclamp((n + 2047) / 2048, 1024); }
 
-void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, uint32_t* chunk_words,
-                   uint32_t* hist_part, unsigned long long* hist_max, uint8_t* huff_lens,
-                   uint32_t* huff_maxd, uint8_t* out, uint64_t cap, unsigned long long* offs,
-                   uint32_t* err, bool hist_done, hipStream_t s) {
+uint32_t enc_slot_words(bool is64, int chunk_log2) {
+  // per symbol at most the longest code and, for values from kDirect up, one
+  // raw bit fewer than the value's width
+  return (uint32_t)(((1ull << chunk_log2) * (uint64_t)(kMaxLen + (is64 ? 63 : 31)) + 31) / 32);
+}
+uint64_t enc_stage_words(uint64_t n, bool is64, int chunk_log2) {
+  return ((n + (1ull << chunk_log2) - 1) >> chunk_log2) * enc_slot_words(is64, chunk_log2);
+}
+
+void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncScratch& X,
+                   uint8_t* out, uint64_t cap, unsigned long long* offs, uint32_t* err,
+                   bool hist_done, hipStream_t s) {
   const int NA = L.NA;
   const uint32_t* pre_hist = L.pre;
   const uint32_t* pre_chunk = L.pre + (NA + 1);
   const uint32_t* pre_fixed = L.pre + 2 * (NA + 1);
+  const uint32_t* pre_copy = L.pre + 3 * (NA + 1);
   if (!hist_done)
     LCP_TIMED("hist", L.values * 4ull, s,
-              k_hist<<<L.hist_blocks, kThreads, 0, s>>>(L.arrs, pre_hist, NA, hist_part, hist_max));
+              k_hist<<<L.hist_blocks, kThreads, 0, s>>>(L.arrs, pre_hist, NA, X.hist_part,
+                                                        X.hist_max));
   // the plain build (and its codes) per array; the halving candidates and their
-  // codes only run for arrays whose plain build is too deep
-  // Temporal residual arrays (hist_done) halve inline: their alphabets are
-  // short and the fallback launches would cost more than they save.
-  k_huff_build<<<NA, kHT, 0, s>>>(L.arrs, hist_part, hist_max, work, huff_lens, huff_maxd,
-                                  hist_done ? 1 : 0);
+  // codes only run for arrays whose plain build is too deep.  Temporal residual
+  // arrays (hist_done) halve inline: their alphabets are short and the fallback
+  // launches would cost more than they save.
+  k_huff_build<<<NA, kHT, 0, s>>>(L.arrs, X.hist_part, X.hist_max, work, X.huff_lens, X.huff_maxd,
+                                  hist_done ? 1 : 0, chunk_log2);
   if (!hist_done) {
-    k_huff_lengths<<<dim3(NA, kHalvings - 1), kHT, 0, s>>>(work, huff_lens, huff_maxd);
-    k_huff_codes<<<NA, kHT, 0, s>>>(work, huff_lens, huff_maxd);
+    k_huff_lengths<<<dim3(NA, kHalvings - 1), kHT, 0, s>>>(work, X.huff_lens, X.huff_maxd);
+    k_huff_codes<<<NA, kHT, 0, s>>>(L.arrs, work, X.huff_lens, X.huff_maxd, chunk_log2);
   }
-  LCP_TIMED("chunk_bits", L.values * 4ull, s, {
-    switch (chunk_log2) {
-      case 9: k_chunk_bits<2><<<L.chunk_blocks, kThreads, 0, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, chunk_words); break;
-      case 10: k_chunk_bits<4><<<L.chunk_blocks, kThreads, 0, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, chunk_words); break;
-      case 11: k_chunk_bits<8><<<L.chunk_blocks, kThreads, 0, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, chunk_words); break;
-      case 12: k_chunk_bits<16><<<L.chunk_blocks, kThreads, 0, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, chunk_words); break;
-      default: k_chunk_bits<1><<<L.chunk_blocks, kThreads, 0, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, chunk_words); break;
-    }
-  });
-  k_chunk_scan<<<NA, kHT, 0, s>>>(L.arrs, work, chunk_log2, chunk_words);
+  const uint32_t slot32 = enc_slot_words(false, chunk_log2), slot64 = enc_slot_words(true, chunk_log2);
+  {
+    const size_t shm = (size_t)slot64 * 4;
+    const uint32_t g = L.chunk_blocks;
+    LCP_TIMED("pack_huff", L.values * 6ull, s, {
+      switch (chunk_log2) {
+        case 9: k_pack_huff<2><<<g, kThreads, shm, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, slot64, err); break;
+        case 10: k_pack_huff<4><<<g, kThreads, shm, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, slot64, err); break;
+        case 11: k_pack_huff<8><<<g, kThreads, shm, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, slot64, err); break;
+        case 12: k_pack_huff<16><<<g, kThreads, shm, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, slot64, err); break;
+        default: k_pack_huff<1><<<g, kThreads, shm, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, slot64, err); break;
+      }
+    });
+  }
   k_layout<<<1, kHT, 0, s>>>(work, L.recs, L.R, out, cap, offs, err);
   LCP_TIMED("pack_fixed", L.values * 6ull, s,
             k_pack_fixed<<<L.fixed_blocks, kThreads, 0, s>>>(L.arrs, work, L.recs, pre_fixed, NA,
                                                              out, err));
-  {
-    const uint32_t C = 1u << chunk_log2;
-    const uint32_t max_words = (C * (kMaxLen + 63) + 31) / 32 + 1;
-    const size_t shm = (size_t)max_words * 4;
-    const uint32_t g = L.chunk_blocks;
-    LCP_TIMED("pack_huff", L.values * 6ull, s, {
-      switch (chunk_log2) {
-        case 9: k_pack_huff<2><<<g, kThreads, shm, s>>>(L.arrs, work, L.recs, pre_chunk, NA, chunk_log2, chunk_words, max_words, out, err); break;
-        case 10: k_pack_huff<4><<<g, kThreads, shm, s>>>(L.arrs, work, L.recs, pre_chunk, NA, chunk_log2, chunk_words, max_words, out, err); break;
-        case 11: k_pack_huff<8><<<g, kThreads, shm, s>>>(L.arrs, work, L.recs, pre_chunk, NA, chunk_log2, chunk_words, max_words, out, err); break;
-        case 12: k_pack_huff<16><<<g, kThreads, shm, s>>>(L.arrs, work, L.recs, pre_chunk, NA, chunk_log2, chunk_words, max_words, out, err); break;
-        default: k_pack_huff<1><<<g, kThreads, shm, s>>>(L.arrs, work, L.recs, pre_chunk, NA, chunk_log2, chunk_words, max_words, out, err); break;
-      }
-    });
-  }
+  k_copy_huff<<<L.copy_blocks, kThreads, 0, s>>>(L.arrs, work, L.recs, pre_copy, NA,
+                                                  X.chunk_words, X.stage, slot32, slot64, out, err);
 }
 
 uint32_t decode_blocks(const DecArr& d, int chunk_log2, bool huff) {

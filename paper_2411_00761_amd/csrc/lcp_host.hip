@@ -76,7 +76,7 @@ struct lcp_plan_s {
   uint64_t NB = 0;  // max particles per spatial batch (>= N)
   int RB = 1;       // max frames per spatial batch
   int NAmax = 0;    // max coded arrays per encode launch set
-  uint64_t hist_copies = 0, cw_cap = 0;
+  uint64_t hist_copies = 0, cw_cap = 0, stage_cap = 0;
   // memory: scratch (device + pinned host tables) is either owned (standalone
   // plans) or bound per call by a server; the stream state is always owned
   void* own_dev = nullptr;   // owned device scratch block
@@ -87,6 +87,7 @@ struct lcp_plan_s {
   // scratch (batch-wide arrays hold NB slots)
   uint64_t *keys0, *keys1, *ids, *v_id, *v_cnt, *prel;
   uint32_t *vals0, *vals1, *hist, *flags, *starts, *v_slot, *chunk_words, *lut, *corner;
+  uint32_t* stage;  // Huffman payload staging, one slot per chunk
   uint64_t* scan_tmp;
   size_t scan_tmp_n;
   ArrWork* work;
@@ -115,7 +116,7 @@ struct lcp_plan_s {
   // encoder tables
   EncArr *earr_host, *earr_dev;
   EncRec *erec_host, *erec_dev;
-  uint32_t *epre_host, *epre_dev;  // [3][NAmax + 1]
+  uint32_t *epre_host, *epre_dev;  // [4][NAmax + 1]
   unsigned long long* offs_dev;  // [RB + 1] record offsets (in ret_dev)
   // batched decode staging (pinned host + device mirrors)
   uint8_t *hdr_host, *hdr_dev;
@@ -355,8 +356,8 @@ lcp_status field_eb(const lcp_params& p, int F, const float* lo, const float* hi
 struct EncBuild {
   int NA = 0, R = 0;
   uint32_t copies = 0;
-  uint64_t cw = 0, values = 0;
-  std::vector<uint32_t> hb, cb, fb;
+  uint64_t cw = 0, values = 0, stage = 0;
+  std::vector<uint32_t> hb, cb, fb, kb;
 };
 
 // Adds one array of at most nb values to record rec; copy0 < 0 places its
@@ -379,9 +380,12 @@ lcp_status enc_add(lcp_plan_s* P, EncBuild& B, const ArrIn& in, uint64_t nb, int
   }
   e.cw0 = B.cw;
   B.cw += (nb + (1ull << P->chunk_log2) - 1) >> P->chunk_log2;
-  if (B.copies > P->hist_copies || B.cw > P->cw_cap) return LCP_ERR_ARG;
+  e.stage0 = B.stage;
+  B.stage += enc_stage_words(nb, in.is64 != 0, P->chunk_log2);
+  if (B.copies > P->hist_copies || B.cw > P->cw_cap || B.stage > P->stage_cap) return LCP_ERR_ARG;
   B.hb.push_back(enc_hist_blocks(nb));
   B.cb.push_back(enc_chunk_blocks(nb, P->chunk_log2));
+  B.kb.push_back(enc_copy_blocks(nb, P->chunk_log2));
   B.fb.push_back(enc_fixed_blocks(nb));
   B.values += nb;
   B.NA++;
@@ -400,29 +404,40 @@ lcp_status enc_launch(lcp_plan_s* P, EncBuild& B, uint8_t* out, uint64_t cap, bo
   uint32_t* ph = P->epre_host;
   uint32_t* pc = ph + (NA + 1);
   uint32_t* pf = pc + (NA + 1);
-  uint32_t h = 0, c = 0, f = 0;
+  uint32_t* pk = pf + (NA + 1);
+  uint32_t h = 0, c = 0, f = 0, k = 0;
   for (int a = 0; a < NA; a++) {
     ph[a] = h;
     pc[a] = c;
     pf[a] = f;
+    pk[a] = k;
     h += B.hb[a];
     c += B.cb[a];
     f += B.fb[a];
+    k += B.kb[a];
   }
   ph[NA] = h;
   pc[NA] = c;
   pf[NA] = f;
+  pk[NA] = k;
   L.hist_blocks = h;
   L.chunk_blocks = c;
   L.fixed_blocks = f;
+  L.copy_blocks = k;
   L.values = B.values;
   lcp_status st = upload_group({{P->erec_host, P->erec_dev, sizeof(EncRec) * B.R},
                                  {P->earr_host, P->earr_dev, sizeof(EncArr) * NA},
-                                 {P->epre_host, P->epre_dev, sizeof(uint32_t) * 3 * (NA + 1)}},
+                                 {P->epre_host, P->epre_dev, sizeof(uint32_t) * 4 * (NA + 1)}},
                                 s);
   if (st) return st;
-  launch_encode(L, P->chunk_log2, P->work, P->chunk_words, P->hist_part, P->hist_max,
-                P->huff_lens, P->huff_maxd, out, cap, P->offs_dev, P->err, hist_done, s);
+  EncScratch X;
+  X.chunk_words = P->chunk_words;
+  X.stage = P->stage;
+  X.hist_part = P->hist_part;
+  X.hist_max = P->hist_max;
+  X.huff_lens = P->huff_lens;
+  X.huff_maxd = P->huff_maxd;
+  launch_encode(L, P->chunk_log2, P->work, X, out, cap, P->offs_dev, P->err, hist_done, s);
   return LCP_OK;
 }
 
@@ -435,6 +450,8 @@ lcp_status finish_records(lcp_plan_s* P, int R, uint64_t* offs, uint32_t* flags,
   for (int r = 0; r <= R; r++) offs[r] = P->ret_host[1 + r];
   if (flags) *flags = host_err(P);
   if (host_err(P) & kErrCapacity) return LCP_ERR_CAPACITY;
+  // the encoder's own consistency checks (a chunk beyond its staging slot)
+  if (host_err(P) & kErrCorrupt) return LCP_ERR_DEVICE;
   return LCP_OK;
 }
 
@@ -1255,6 +1272,12 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   if (hc < (uint64_t)kMaxF * kHistCopies) hc = (uint64_t)kMaxF * kHistCopies;
   P->hist_copies = hc;
   P->cw_cap = (uint64_t)(F + 2) * NB / (1ull << P->chunk_log2) + NA + 1;
+  // staging: enc_stage_words summed over a batch's arrays; per array type a
+  // batch has at most NB / C + RB chunks (ids and counts are 64-bit, the rest
+  // 32-bit)
+  P->stage_cap = ((uint64_t)2 * enc_slot_words(true, P->chunk_log2) +
+                  (uint64_t)F * enc_slot_words(false, P->chunk_log2)) *
+                 ((NB >> P->chunk_log2) + RB + 1);
   uint64_t sn = NB > 256 * ntiles ? NB : 256 * ntiles;
   P->scan_tmp_n = scan_tmp_elems(sn);
   P->rec_tmp_cap = bound_bytes(F, N);
@@ -1271,6 +1294,7 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   D.add(&P->starts, NB);
   D.add(&P->v_slot, (uint64_t)F * NB);
   D.add(&P->chunk_words, P->cw_cap);
+  D.add(&P->stage, P->stage_cap);
   D.add(&P->lut, (uint64_t)(kMaxBatchArrays + 2 * kMaxBatchFrames) << kMaxLen);
   D.add(&P->ext_part, (uint64_t)2 * kMaxF * kSegExtCap * RB);
   D.add(&P->hist_part, hc * kAlphabet);
@@ -1293,7 +1317,7 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   D.add(&P->dpre_dev, 2 * (kMaxBatchFrames + 1));
   D.add(&P->erec_dev, RB);
   D.add(&P->earr_dev, NA);
-  D.add(&P->epre_dev, 3 * (NA + 1));
+  D.add(&P->epre_dev, 4 * (NA + 1));
   D.add(&P->rstart, (uint64_t)RB + 1);
   D.add(&P->Bs, RB);
   D.add(&P->permdst_dev, RB);
@@ -1310,7 +1334,7 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   H.add(&P->dpre_host, 2 * (kMaxBatchFrames + 1));
   H.add(&P->erec_host, RB);
   H.add(&P->earr_host, NA);
-  H.add(&P->epre_host, 3 * (NA + 1));
+  H.add(&P->epre_host, 4 * (NA + 1));
   H.add(&P->permdst_host, RB);
 }
 

@@ -42,6 +42,8 @@ struct ArrWork {
   unsigned long long maxv;
   uint32_t n, U, L, coder, w, nchunks;
   unsigned long long huff_words, nbytes, off;
+  unsigned long long huff_bits;  // code + raw bits of all symbols (no chunk padding)
+  uint32_t cand, pad;            // Huffman may be the shorter coding: pack it
 };
 
 // Header fields of a record being written.
@@ -61,7 +63,8 @@ struct EncArr {
   uint32_t copy0;   // first of its spread histogram copies in hist_part
   uint32_t copies;  // number of spread copies
   uint32_t pad;
-  uint64_t cw0;     // first of its chunk word counts in chunk_words
+  uint64_t cw0;     // first of its chunk words / look-back states
+  uint64_t stage0;  // first word of its Huffman payload staging
 };
 struct EncRec {
   RecHdr h;
@@ -69,12 +72,15 @@ struct EncRec {
   uint32_t a0, pad;       // first array of the record
   unsigned long long size, off;  // written by the layout kernel
 };
-// Workgroups given to an array of (at most) n values in each encode launch, and
-// its spread histogram copies.
+// Workgroups given to an array of (at most) n values in each encode launch, its
+// spread histogram copies, and its Huffman payload staging (words).
 uint32_t enc_hist_blocks(uint64_t n);
 uint32_t enc_hist_copies(uint64_t n);
 uint32_t enc_chunk_blocks(uint64_t n, int chunk_log2);
+uint32_t enc_copy_blocks(uint64_t n, int chunk_log2);
 uint32_t enc_fixed_blocks(uint64_t n);
+uint32_t enc_slot_words(bool is64, int chunk_log2);
+uint64_t enc_stage_words(uint64_t n, bool is64, int chunk_log2);
 
 // One frame of a spatial batch (device table).  Frames are concatenated: frame
 // r owns slots [off, off + n) of every batch-wide array.  Per-particle kernels
@@ -260,13 +266,22 @@ struct EncLaunch {
   EncRec* recs;
   const uint32_t* pre;
   int NA, R;
-  uint32_t hist_blocks, chunk_blocks, fixed_blocks;
+  uint32_t hist_blocks, chunk_blocks, fixed_blocks, copy_blocks;
   uint64_t values;  // sum of the arrays' lengths (bounds), for the kernel timer
 };
-void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, uint32_t* chunk_words,
-                   uint32_t* hist_part, unsigned long long* hist_max, uint8_t* huff_lens,
-                   uint32_t* huff_maxd, uint8_t* out, uint64_t cap, unsigned long long* offs,
-                   uint32_t* err, bool hist_done, hipStream_t s);
+// Coding scratch of a launch set: a word count per chunk and the staging of
+// the Huffman payloads before they move into their records.
+struct EncScratch {
+  uint32_t* chunk_words;  // word count per chunk
+  uint32_t* stage;        // one slot per chunk (enc_slot_words)
+  uint32_t* hist_part;
+  unsigned long long* hist_max;
+  uint8_t* huff_lens;
+  uint32_t* huff_maxd;
+};
+void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncScratch& X,
+                   uint8_t* out, uint64_t cap, unsigned long long* offs, uint32_t* err,
+                   bool hist_done, hipStream_t s);
 // Workgroups needed by one array in the Huffman (huff=true) or fixed-length
 // decode launch (0 when the array uses the other coder).
 uint32_t decode_blocks(const DecArr& d, int chunk_log2, bool huff);
