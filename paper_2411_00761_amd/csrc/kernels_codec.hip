@@ -824,6 +824,7 @@ __device__ inline void write_header(const RecHdr& h, uint64_t B, uint64_t size, 
 
 __global__ __launch_bounds__(kHT) void k_layout(ArrWork* W, EncRec* recs, int R, uint8_t* out,
                                                 uint64_t cap, unsigned long long* offs,
+                                                const unsigned long long* base_dev,
                                                 uint32_t* err) {
   __shared__ unsigned long long sm[kHT / kWave + 1];
   __shared__ uint32_t s_a0[kLayRecs];
@@ -832,7 +833,7 @@ __global__ __launch_bounds__(kHT) void k_layout(ArrWork* W, EncRec* recs, int R,
   __shared__ unsigned long long s_roff[kLayRecs], s_size[kLayRecs];
   const int t = (int)threadIdx.x;
   const int j = t / kMaxArrays, a = t % kMaxArrays;
-  unsigned long long carry = 0;
+  unsigned long long carry = base_dev ? *base_dev : 0ull;
   for (int base = 0; base < R; base += kLayRecs) {
     const int r = base + t;
     const bool hv = t < kLayRecs && r < R;
@@ -1491,7 +1492,7 @@ uint64_t enc_stage_words(uint64_t n, bool is64, int chunk_log2) {
 
 void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncScratch& X,
                    uint8_t* out, uint64_t cap, unsigned long long* offs, uint32_t* err,
-                   bool hist_done, hipStream_t s) {
+                   const unsigned long long* base, bool hist_done, hipStream_t s) {
   const int NA = L.NA;
   const uint32_t* pre_hist = L.pre;
   const uint32_t* pre_chunk = L.pre + (NA + 1);
@@ -1525,7 +1526,7 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
       }
     });
   }
-  k_layout<<<1, kHT, 0, s>>>(work, L.recs, L.R, out, cap, offs, err);
+  k_layout<<<1, kHT, 0, s>>>(work, L.recs, L.R, out, cap, offs, base, err);
   LCP_TIMED("pack_fixed", L.values * 6ull, s,
             k_pack_fixed<<<L.fixed_blocks, kThreads, 0, s>>>(L.arrs, work, L.recs, pre_fixed, NA,
                                                              out, err));

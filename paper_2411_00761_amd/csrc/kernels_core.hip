@@ -230,10 +230,12 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
                                                       int32_t* q_new, uint32_t* err, int vec,
                                                       uint32_t* hist_part,
                                                       unsigned long long* hist_max) {
-  __shared__ uint32_t bins[kMaxF][kThreads / kWave][kResPriv];
+  // per field and wave kResPriv private bins, sized by F at launch so that
+  // LDS does not cap the workgroups resident per CU
+  extern __shared__ uint32_t bins_lds[];
   __shared__ uint32_t smax[kMaxF][kThreads / kWave];
-  for (int j = threadIdx.x; j < F * (kThreads / kWave) * kResPriv; j += kThreads)
-    (&bins[0][0][0])[j] = 0;
+  auto bins = [&](int f, int w) { return bins_lds + ((uint32_t)f * (kThreads / kWave) + w) * kResPriv; };
+  for (int j = threadIdx.x; j < F * (kThreads / kWave) * kResPriv; j += kThreads) bins_lds[j] = 0;
   __syncthreads();
   const int copy = blockIdx.x % kHistCopies;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -245,7 +247,7 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
   auto count = [&](int f, uint32_t r) {
     uint32_t* shared = hist_part + ((uint64_t)f * kHistCopies + copy) * kAlphabet;
     int e;
-    wave_hist_add(shared, bins[f][wave_id()], kResPriv, (uint32_t)symbol_of(r, &e), true);
+    wave_hist_add(shared, bins(f, wave_id()), kResPriv, (uint32_t)symbol_of(r, &e), true);
   };
   if (vec) {  // n % 4 == 0 and 16-byte aligned arrays: 4 slots per thread
     for (uint64_t s4 = gid; s4 < n / 4; s4 += stride) {
@@ -302,7 +304,7 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
     uint32_t* shared = hist_part + ((uint64_t)f * kHistCopies + copy) * kAlphabet;
     for (int j = threadIdx.x; j < kResPriv; j += kThreads) {
       uint32_t t = 0;
-      for (int w = 0; w < kThreads / kWave; w++) t += bins[f][w][j];
+      for (int w = 0; w < kThreads / kWave; w++) t += bins(f, w)[j];
       if (t) atomicAdd(&shared[j], t);
     }
     if (threadIdx.x == 0) {
@@ -311,6 +313,26 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
       if (m) atomicMax(&hist_max[(uint64_t)f * kHistCopies + copy], (unsigned long long)m);
     }
   }
+}
+
+// The codes a temporal frame leaves as the next frame's reference: the frame's
+// Eq. 5 codes on its reference grid, in the reference's slot order.  They
+// depend on the frame, the grid and the slot order only (not on the
+// reference's codes), so they can be rebuilt when their slot was reused.
+__global__ __launch_bounds__(kThreads) void k_t_codes(FieldPtrs x, int F, uint64_t n, GridDev g,
+                                                      const uint32_t* perm_ref, int32_t* q_new,
+                                                      uint32_t* err) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint32_t bad = 0;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
+    const uint32_t i = perm_ref[s];
+    for (int f = 0; f < F; f++) {
+      int64_t q;
+      t_code(x.p[f][i], g, f, &bad, &q);
+      q_new[(uint64_t)f * n + s] = (int32_t)q;
+    }
+  }
+  if (bad) atomicOr(err, bad);
 }
 
 // ------------------------------------------------------------------ spatial batch
@@ -982,8 +1004,15 @@ void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
                     unsigned long long* hist_max, hipStream_t s) {
   const int vec = (n % 4 == 0) && al16(perm_ref) && al16(q_ref) && al16(v_res) && al16(q_new);
   LCP_TIMED("t_resid", n * (4 + 16ull * F), s,
-            k_t_resid<<<grid_for(vec ? n / 4 : n, kThreads * 2, 2048), kThreads, 0, s>>>(
+            k_t_resid<<<grid_for(vec ? n / 4 : n, kThreads * 2, 2048), kThreads,
+                        (size_t)F * (kThreads / kWave) * kResPriv * 4, s>>>(
                 x, F, n, g, perm_ref, q_ref, v_res, q_new, err, vec, hist_part, hist_max));
+}
+
+void launch_t_codes(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
+                    const uint32_t* perm_ref, int32_t* q_new, uint32_t* err, hipStream_t s) {
+  k_t_codes<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(x, F, n, g, perm_ref, q_new,
+                                                                      err);
 }
 
 void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, uint64_t B,

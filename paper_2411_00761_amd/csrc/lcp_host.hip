@@ -16,6 +16,9 @@ using namespace lcp;
 
 namespace {
 
+// Temporal frames coded back to back before the host reads their outcomes.
+constexpr int kTRun = 8;
+
 // ------------------------------------------------------------------ grids
 struct HostGrid {
   float m, eb_q;
@@ -96,6 +99,9 @@ struct lcp_plan_s {
   unsigned long long *ret_dev, *ret_host;
   uint32_t* err;  // the error word (low half of ret_dev[0])
   bool err_clean = false;  // the error word is known to be zero at the stream's tail
+  // temporal runs (frames coded back to back, one read-back per run): per
+  // frame [4k] error word, [4k + 1, 4k + 3) record start and end
+  unsigned long long *run_dev, *run_host;
   uint8_t* rec_tmp;  // second record (temporal candidate)
   uint64_t rec_tmp_cap;
   uint32_t* ext_part;    // extent partials
@@ -392,8 +398,11 @@ lcp_status enc_add(lcp_plan_s* P, EncBuild& B, const ArrIn& in, uint64_t nb, int
   return LCP_OK;
 }
 
+// Errors go to err and record offsets to offs (the plan's return block unless
+// given); with base (device) the first record starts at *base.
 lcp_status enc_launch(lcp_plan_s* P, EncBuild& B, uint8_t* out, uint64_t cap, bool hist_done,
-                      hipStream_t s) {
+                      hipStream_t s, uint32_t* err = nullptr, unsigned long long* offs = nullptr,
+                      const unsigned long long* base = nullptr) {
   const int NA = B.NA;
   EncLaunch L;
   L.arrs = P->earr_dev;
@@ -437,7 +446,8 @@ lcp_status enc_launch(lcp_plan_s* P, EncBuild& B, uint8_t* out, uint64_t cap, bo
   X.hist_max = P->hist_max;
   X.huff_lens = P->huff_lens;
   X.huff_maxd = P->huff_maxd;
-  launch_encode(L, P->chunk_log2, P->work, X, out, cap, P->offs_dev, P->err, hist_done, s);
+  launch_encode(L, P->chunk_log2, P->work, X, out, cap, offs ? offs : P->offs_dev,
+                err ? err : P->err, base, hist_done, s);
   return LCP_OK;
 }
 
@@ -607,21 +617,31 @@ lcp_status extent(lcp_plan_s* P, const float* const* x, uint64_t n, float* lo, f
 // LCP-T on one frame against a resident reference.  Whether the frame fits the
 // reference grid (finite values, float32 margin, code range) is checked by the
 // residual kernel itself, so no extent pass is needed.
-lcp_status compress_t(lcp_plan_s* P, const float* const* x, uint64_t n, const RefState& ref,
-                      uint64_t seq, uint8_t* out, uint64_t cap, int32_t* q_new, uint64_t* size,
-                      hipStream_t s) {
-  const int F = P->F;
-  FieldPtrs fp;
-  memset(&fp, 0, sizeof(fp));
-  for (int f = 0; f < F; f++) fp.p[f] = x[f];
+GridDev t_grid(const RefState& ref, int F) {
   GridDev gd = to_dev(ref.grid, F);
   for (int f = 0; f < F; f++) {
     gd.eb2[f] = 2.0 * ref.grid[f].eb;
     gd.lim[f] = ldexp(1.0, ref.grid[f].E);
   }
-  clear_err(P, s);
-  launch_t_resid(fp, F, n, gd, P->ppool[ref.perm], P->qpool[ref.q], P->v_slot, q_new,
-                 P->err, P->hist_part, P->hist_max, s);
+  return gd;
+}
+
+FieldPtrs field_ptrs(const float* const* x, int F) {
+  FieldPtrs fp;
+  memset(&fp, 0, sizeof(fp));
+  for (int f = 0; f < F; f++) fp.p[f] = x[f];
+  return fp;
+}
+
+// Enqueues LCP-T of one frame against `ref` (Sec. 4): residual kernel, then
+// the coder launches.  Errors go to err, the record's start and end to
+// offs[0..1] (from *base when given).
+lcp_status launch_t(lcp_plan_s* P, const float* const* x, uint64_t n, const RefState& ref,
+                    uint64_t seq, uint8_t* out, uint64_t cap, int32_t* q_new, uint32_t* err,
+                    unsigned long long* offs, const unsigned long long* base, hipStream_t s) {
+  const int F = P->F;
+  launch_t_resid(field_ptrs(x, F), F, n, t_grid(ref, F), P->ppool[ref.perm], P->qpool[ref.q],
+                 P->v_slot, q_new, err, P->hist_part, P->hist_max, s);
   EncBuild B;
   B.R = 1;
   EncRec& rc = P->erec_host[0];
@@ -634,7 +654,15 @@ lcp_status compress_t(lcp_plan_s* P, const float* const* x, uint64_t n, const Re
     if ((st = enc_add(P, B, ArrIn{P->v_slot + (uint64_t)f * n, 0, nullptr, n}, n, 0,
                       f * kHistCopies, kHistCopies)))
       return st;
-  if ((st = enc_launch(P, B, out, cap, true, s))) return st;
+  return enc_launch(P, B, out, cap, true, s, err, offs, base);
+}
+
+lcp_status compress_t(lcp_plan_s* P, const float* const* x, uint64_t n, const RefState& ref,
+                      uint64_t seq, uint8_t* out, uint64_t cap, int32_t* q_new, uint64_t* size,
+                      hipStream_t s) {
+  clear_err(P, s);
+  lcp_status st = launch_t(P, x, n, ref, seq, out, cap, q_new, P->err, P->offs_dev, nullptr, s);
+  if (st) return st;
   uint32_t flags = 0;
   uint64_t offs[2] = {0, 0};
   st = finish_records(P, 1, offs, &flags, s);
@@ -814,6 +842,105 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
     launch_copy_perm(src, perm_out, n, s);
   }
   P->seq++;
+  return LCP_OK;
+}
+
+// ------------------------------------------------------------------ temporal runs
+// While LCP-FSM stays in its T state every frame is coded with LCP-T against
+// the frame before it (Alg. 1: the batch anchor for the first frame of a
+// batch), and the host only needs a frame's outcome to learn that it still
+// holds.  A run therefore enqueues up to kTRun such frames back to back, each
+// with its own error word and offsets, each record placed on the device right
+// behind the previous one, and reads the outcomes back once.  Frames are then
+// taken in order; the first whose outcome differs from the prediction (an
+// error flag, a record beyond capacity, a size above the last spatial one) and
+// every frame after it are left to the per-frame path, which codes that frame
+// again from the state the run committed.  Codes of a run frame go to one of
+// the two q slots that are neither the committed reference nor the anchor,
+// alternating, so the committed reference survives the run; the last
+// committed frame's codes, if a later frame reused their slot, are rebuilt
+// from its input.
+struct RunFrame {
+  RefState ref;  // reference the frame is coded against
+  int q;         // q slot of its codes
+};
+
+// Frames that would be coded as T in a row if each of them stays T.
+int plan_run(const lcp_plan_s* P, const lcp_frame_in* fr, uint64_t nf, uint64_t cap,
+             RunFrame* rf) {
+  if (!P->p.multi_frame) return 0;
+  int spare[2], ns = 0;
+  for (int i = 0; i < 4 && ns < 2; i++)
+    if (!(P->prev.valid && P->prev.q == i) && !(P->anchor.valid && P->anchor.q == i))
+      spare[ns++] = i;
+  if (ns < 2) return 0;
+  RefState prev = P->prev;
+  uint64_t seq = P->seq, used = 0;
+  int D = 0;
+  for (; D < kTRun && (uint64_t)D < nf; D++) {
+    const lcp_frame_in& f = fr[D];
+    if (f.n == 0 || f.n > P->N || f.method < 0 || f.method > 2) break;
+    bool ok = true;
+    for (int k = 0; k < P->F; k++) ok = ok && f.fields[k] != nullptr;
+    if (!ok) break;
+    if (f.method == LCP_METHOD_S || (f.method == LCP_METHOD_AUTO && !P->fsm_t)) break;
+    const bool first = P->p.batch_size == 0 ? seq == 0 : seq % (uint64_t)P->p.batch_size == 0;
+    const RefState& ref = first ? P->anchor : prev;
+    if (!ref.valid || ref.n != f.n) break;
+    used += bound_bytes(P->F, f.n);
+    if (used > cap) break;
+    rf[D].ref = ref;
+    rf[D].q = spare[D & 1];
+    RefState r = ref;
+    r.seq = seq;
+    r.q = rf[D].q;
+    prev = r;
+    seq++;
+  }
+  return D;
+}
+
+// Runs D planned frames; ends[k] receives frame k's record end (relative to
+// out) for the committed frames, *committed how many there are.
+lcp_status run_t(lcp_plan_s* P, const lcp_frame_in* fr, int D, const RunFrame* rf, uint8_t* out,
+                 uint64_t cap, uint32_t* const* perms, uint64_t* ends, int* committed,
+                 hipStream_t s) {
+  *committed = 0;
+  launch_fill_u32(reinterpret_cast<uint32_t*>(P->run_dev), 8ull * D, 0u, s);
+  for (int k = 0; k < D; k++) {
+    unsigned long long* slot = P->run_dev + 4 * k;
+    lcp_status st = launch_t(P, fr[k].fields, fr[k].n, rf[k].ref, P->seq + k, out, cap,
+                             P->qpool[rf[k].q], reinterpret_cast<uint32_t*>(slot), slot + 1,
+                             k ? P->run_dev + 4 * (k - 1) + 2 : nullptr, s);
+    if (st) return st;
+  }
+  HIP_OK(hipMemcpyAsync(P->run_host, P->run_dev, 32ull * D, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  int c = 0;
+  for (; c < D; c++) {
+    const uint32_t flags = (uint32_t)(P->run_host[4 * c] & 0xFFFFFFFFull);
+    const uint64_t start = P->run_host[4 * c + 1], end = P->run_host[4 * c + 2];
+    const uint64_t size = end - start;
+    if (flags) break;
+    if (fr[c].method == LCP_METHOD_AUTO && (!P->have_last_s || size > P->last_s)) break;
+    // committed: LCP-FSM stays in T; Alg. 1 bookkeeping as for any T frame
+    RefState r = rf[c].ref;
+    r.seq = P->seq;
+    r.q = rf[c].q;
+    P->prev = r;
+    if (perms && perms[c]) launch_copy_perm(P->ppool[r.perm], perms[c], fr[c].n, s);
+    P->seq++;
+    ends[c] = end;
+  }
+  *committed = c;
+  // the last committed frame's codes were overwritten if the frame two after
+  // it was launched
+  if (c >= 1 && c + 1 < D) {
+    const int F = P->F;
+    launch_t_codes(field_ptrs(fr[c - 1].fields, F), F, fr[c - 1].n, t_grid(P->prev, F),
+                   P->ppool[P->prev.perm], P->qpool[P->prev.q], P->err, s);
+    P->err_clean = false;
+  }
   return LCP_OK;
 }
 
@@ -1309,6 +1436,7 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   D.add(&P->scan_tmp, P->scan_tmp_n);
   D.add(&P->work, NA);
   D.add(&P->ret_dev, 2 + (uint64_t)RB + (uint64_t)RB * F);
+  D.add(&P->run_dev, 4 * kTRun);
   // tables uploaded together are adjacent, with the same sizes as their host
   // staging (seg + segpre, dseg + dpre, erec + earr + epre)
   D.add(&P->seg_dev, RB);
@@ -1324,6 +1452,7 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   D.add(&P->segbase, 3 * kMaxBatchFrames);
   D.add(&P->rec_tmp, P->rec_tmp_cap);
   H.add(&P->ret_host, 2 + (size_t)RB + (size_t)RB * F);
+  H.add(&P->run_host, 4 * kTRun);
   H.add(&P->hdr_host, (size_t)kHdrStage * kMaxBatchFrames);
   H.add(&P->blobtab_host, 2 * kMaxBatchFrames);
   H.add(&P->arrtab_host, kMaxBatchArrays + 2 * kMaxBatchFrames);
@@ -1690,6 +1819,7 @@ lcp_status lcp_compress(lcp_plan_t plan, uint64_t n_frames, const lcp_frame_in* 
                                      perms ? perms + j : nullptr, stream);
       if (st == LCP_ERR_CAPACITY) {
         for (int r = 0; r < R; r++) out_offsets[j + r + 1] = off + offs[r + 1];
+        out_offsets[n_frames] = off + offs[R];  // the bytes required so far
         return st;
       }
       if (st) return st;
@@ -1703,19 +1833,40 @@ lcp_status lcp_compress(lcp_plan_t plan, uint64_t n_frames, const lcp_frame_in* 
     timer_collect(plan);
     return LCP_OK;
   }
-  for (uint64_t j = 0; j < n_frames; j++) {
+  bool one = false;  // the next frame goes through the per-frame path
+  for (uint64_t j = 0; j < n_frames;) {
+    uint64_t cap = out_cap > off ? out_cap - off : 0;
+    RunFrame rf[kTRun];
+    const int D = one ? 0 : plan_run(plan, frames + j, n_frames - j, cap, rf);
+    if (D >= 2) {
+      uint64_t ends[kTRun];
+      int c = 0;
+      lcp_status st = run_t(plan, frames + j, D, rf, o + off, cap, perms ? perms + j : nullptr,
+                            ends, &c, stream);
+      if (st) return st;
+      for (int k = 0; k < c; k++) {
+        if (methods_used) methods_used[j + k] = LCP_METHOD_T;
+        out_offsets[j + k + 1] = off + ends[k];
+      }
+      if (c) off += ends[c - 1];
+      j += (uint64_t)c;
+      one = c < D;
+      continue;
+    }
+    one = false;
     uint64_t size = 0;
     int used = 0;
-    uint64_t cap = out_cap > off ? out_cap - off : 0;
     lcp_status st = compress_frame(plan, frames[j], o + off, cap, &size, &used,
                                    perms ? perms[j] : nullptr, stream);
     if (st) {
       out_offsets[j + 1] = off + size;
+      if (st == LCP_ERR_CAPACITY) out_offsets[n_frames] = off + size;
       return st;
     }
     if (methods_used) methods_used[j] = used;
     off += (size + 3) & ~3ull;
     out_offsets[j + 1] = off;
+    j++;
   }
   if (hipStreamSynchronize(stream) != hipSuccess) return LCP_ERR_DEVICE;
   timer_collect(plan);

@@ -224,6 +224,8 @@ void launch_s_recon(const uint32_t* blk, const uint32_t* corner, uint64_t B, int
                     int k, const GridDev& g, const OutPtrs& out, int32_t* q_slot, uint32_t* err,
                     hipStream_t s);
 // out.p[f] holds int32 residuals; q_slot receives q_ref + residual.
+void launch_t_codes(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
+                    const uint32_t* perm_ref, int32_t* q_new, uint32_t* err, hipStream_t s);
 void launch_t_recon(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,
                     const OutPtrs& out, int32_t* q_slot, uint32_t* err, hipStream_t s);
 // Copies `bytes` (a multiple of 4) from host memory to device memory through
@@ -279,9 +281,11 @@ struct EncScratch {
   uint8_t* huff_lens;
   uint32_t* huff_maxd;
 };
+// Records go to out + offs[r]; with `base` (device, nullable) the first
+// record starts at *base rather than at 0, cap bounding the end either way.
 void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncScratch& X,
                    uint8_t* out, uint64_t cap, unsigned long long* offs, uint32_t* err,
-                   bool hist_done, hipStream_t s);
+                   const unsigned long long* base, bool hist_done, hipStream_t s);
 // Workgroups needed by one array in the Huffman (huff=true) or fixed-length
 // decode launch (0 when the array uses the other coder).
 uint32_t decode_blocks(const DecArr& d, int chunk_log2, bool huff);
