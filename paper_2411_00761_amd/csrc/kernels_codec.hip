@@ -755,29 +755,50 @@ __global__ __launch_bounds__(kHT) void k_huff_codes(const EncArr* E, ArrWork* W,
 // with r = C / 256 (at least 1), loaded together.
 constexpr int kMaxRun = 16;  // chunk_log2 <= 12
 
-// Code of a symbol: from the workgroup's LDS copy of the first kPrivBins
-// entries, else from the array's table in global memory.
-__device__ inline uint32_t code_of(const ArrWork& w, const uint32_t* lc_lds, int sym) {
-  return sym < kPrivBins ? lc_lds[sym] : w.lc[sym];
-}
-
+// The array's code table in LDS, up to its largest value's symbol (no symbol
+// above it occurs).
 __device__ inline void load_codes(const ArrWork& w, uint32_t* lc_lds) {
-  for (int j = threadIdx.x; j < kPrivBins; j += blockDim.x) lc_lds[j] = w.lc[j];
+  const int nsym = sym_bound(w.maxv) + 1;
+  for (int j = threadIdx.x; j < nsym; j += blockDim.x) lc_lds[j] = w.lc[j];
 }
 
-template <int RUN>
-__device__ inline uint32_t run_bits(const ArrIn& in, const ArrWork& w, const uint32_t* lc_lds,
-                                    uint64_t i0, uint64_t i1, uint64_t* vals) {
+// Thread t's run of chunk c: values [c*C + t*run, ...) of an array of T.
+// Past the run's end the loads repeat the array's last value (n >= 1): they
+// are unconditional, so they stay in flight until first used, and callers
+// mask them.  Global (not flat) loads, so that waiting for LDS does not wait
+// for them.
+template <int RUN, typename T>
+__device__ inline void load_run(const void* v, uint64_t n, int chunk_log2, uint64_t run,
+                                uint32_t c, uint64_t* vals) {
+  const uint64_t cend = min(n, (uint64_t)(c + 1) << chunk_log2);
+  const uint64_t i0 = min(cend, ((uint64_t)c << chunk_log2) + threadIdx.x * run);
+  const uint64_t last = n - 1;
+  const __attribute__((address_space(1))) T* p = (const __attribute__((address_space(1))) T*)v;
 #pragma unroll
-  for (int j = 0; j < RUN; j++) vals[j] = i0 + j < i1 ? arr_load(in, i0 + j) : 0;
-  uint32_t bits = 0;
+  for (int j = 0; j < RUN; j++) vals[j] = (uint64_t)p[min(i0 + j, last)];
+}
+
+// Workgroup barrier for LDS traffic only: waits for this wave's LDS accesses
+// (global loads stay in flight across it) and for the other waves.  The
+// memory clobber keeps the compiler from moving accesses across it.
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// Inclusive workgroup scan with LDS-only barriers; every thread reads the
+// per-wave totals itself.  `sm` (kThreads / kWave words) must not be written
+// again before another barrier.
+__device__ inline uint32_t block_scan_lds(uint32_t v, uint32_t* sm, uint32_t* total) {
+  const uint32_t x = wave_incl_scan(v);
+  if (lane_id() == kWave - 1) sm[wave_id()] = x;
+  lds_barrier();
+  uint32_t before = 0, tot = 0;
 #pragma unroll
-  for (int j = 0; j < RUN; j++) {
-    int e;
-    int sym = symbol_of(vals[j], &e);
-    if (i0 + j < i1) bits += (code_of(w, lc_lds, sym) >> 16) + (uint32_t)e;
+  for (int w = 0; w < kThreads / kWave; w++) {
+    const uint32_t t = sm[w];
+    before += w < wave_id() ? t : 0u;
+    tot += t;
   }
-  return bits;
+  *total = tot;
+  return x + before;
 }
 
 // ------------------------------------------------------------------ layout
@@ -981,6 +1002,83 @@ struct BitSink {
 // to cnt[c] and, summed per workgroup, into the array's total; where each
 // chunk lands in the record is settled by the copy once all are packed, so no
 // workgroup waits on another.
+// Packs chunk c from its values v (thread t's run) into the chunk's slot.
+template <int RUN>
+__device__ inline void pack_chunk(uint32_t c, const uint64_t* v, uint64_t n, uint64_t C,
+                                  uint64_t run, const uint32_t* lc, uint32_t* buf, uint32_t* sm,
+                                  uint32_t* cnta, uint32_t* pay, uint32_t slot,
+                                  unsigned long long* words, uint32_t* err) {
+  const uint64_t cend = min(n, (uint64_t)(c + 1) * C);
+  const uint64_t i0 = min(cend, (uint64_t)c * C + threadIdx.x * run);
+  const uint64_t i1 = min(cend, i0 + run);
+  uint32_t bits = 0;
+#pragma unroll
+  for (int j = 0; j < RUN; j++) {
+    int ex;
+    const int sym = symbol_of(v[j], &ex);
+    if (i0 + j < i1) bits += (lc[sym] >> 16) + (uint32_t)ex;
+  }
+  uint32_t total;
+  const uint32_t start = block_scan_lds(bits, sm, &total) - bits;
+  const uint32_t nw = (total + 31u) >> 5;
+  // a chunk beyond its slot would mean the code and the data disagree:
+  // flagged, never written
+  const bool fits = nw <= slot;
+  if (threadIdx.x == 0) {
+    if (!fits) atomicOr(err, kErrCorrupt);
+    cnta[c] = nw;
+    *words += nw;
+  }
+  for (uint32_t j = threadIdx.x; j < nw && fits; j += kThreads) buf[j] = 0;
+  lds_barrier();
+  if (bits && fits) {
+    BitSink sk{0ull, (int)(start & 31u), start >> 5, buf};
+#pragma unroll
+    for (int j = 0; j < RUN; j++) {
+      if (i0 + j >= i1) break;
+      int ex;
+      const int sym = symbol_of(v[j], &ex);
+      const uint32_t code = lc[sym];
+      sk.push(code & 0xFFFFu, (int)(code >> 16));
+      if (ex) {
+        const uint64_t x = v[j] - (1ull << ex);
+        if (ex > 32) {
+          sk.push(x >> 32, ex - 32);
+          sk.push(x & 0xFFFFFFFFull, 32);
+        } else {
+          sk.push(x, ex);
+        }
+      }
+    }
+    sk.flush();
+  }
+  lds_barrier();
+  uint32_t* dst = pay + (uint64_t)c * slot;
+  for (uint32_t j = threadIdx.x; j < nw && fits; j += kThreads) dst[j] = buf[j];
+  lds_barrier();
+}
+
+// The workgroup's chunks lb, lb + nb, ... of an array of T, with two value
+// buffers: the next chunk's values are loaded while one is packed.
+template <int RUN, typename T>
+__device__ inline void pack_chunks(const void* v, uint64_t n, int chunk_log2, uint32_t lb,
+                                   uint32_t nb, const uint32_t* lc, uint32_t* buf, uint32_t* sm,
+                                   uint32_t* cnta, uint32_t* pay, uint32_t slot,
+                                   unsigned long long* words, uint32_t* err) {
+  const uint64_t C = 1ull << chunk_log2;
+  const uint32_t nchunks = (uint32_t)((n + C - 1) >> chunk_log2);
+  const uint64_t run = C >= (uint64_t)kThreads ? C / kThreads : 1;
+  uint64_t va[RUN], vb[RUN];
+  load_run<RUN, T>(v, n, chunk_log2, run, min(lb, nchunks - 1), va);
+  for (uint32_t c = lb; c < nchunks; c += 2 * nb) {
+    load_run<RUN, T>(v, n, chunk_log2, run, min(c + nb, nchunks - 1), vb);
+    pack_chunk<RUN>(c, va, n, C, run, lc, buf, sm, cnta, pay, slot, words, err);
+    if (c + nb >= nchunks) break;
+    load_run<RUN, T>(v, n, chunk_log2, run, min(c + 2 * nb, nchunks - 1), va);
+    pack_chunk<RUN>(c + nb, vb, n, C, run, lc, buf, sm, cnta, pay, slot, words, err);
+  }
+}
+
 template <int RUN>
 __global__ __launch_bounds__(kThreads) void k_pack_huff(const EncArr* E, ArrWork* W,
                                                         const uint32_t* pre, int NA,
@@ -988,70 +1086,25 @@ __global__ __launch_bounds__(kThreads) void k_pack_huff(const EncArr* E, ArrWork
                                                         uint32_t* stage, uint32_t slot32,
                                                         uint32_t slot64, uint32_t* err) {
   extern __shared__ uint32_t buf[];
-  __shared__ uint32_t sm[kThreads / kWave + 1];
-  __shared__ uint32_t lc_lds[kPrivBins];
+  __shared__ uint32_t sm[kThreads / kWave];
+  __shared__ uint32_t lc[kAlphabet];
   const uint32_t a = array_of_block(pre, NA, blockIdx.x);
   const uint32_t lb = blockIdx.x - pre[a], nb = pre[a + 1] - pre[a];
   ArrWork& w = W[a];
   if (!w.cand) return;
-  load_codes(w, lc_lds);
+  load_codes(w, lc);
   __syncthreads();
   const EncArr& e = E[a];
-  const ArrIn in = e.in;
   const uint64_t n = w.n;
-  const uint64_t C = 1ull << chunk_log2;
-  const uint32_t nchunks = (uint32_t)((n + C - 1) >> chunk_log2);
-  const uint32_t slot = in.is64 ? slot64 : slot32;
   uint32_t* cnta = cnt + e.cw0;
   uint32_t* pay = stage + e.stage0;
-  const uint64_t run = C >= (uint64_t)kThreads ? C / kThreads : 1;
   unsigned long long words = 0;  // thread 0: this workgroup's share of the array
-  for (uint32_t c = lb; c < nchunks; c += nb) {
-    const uint64_t cend = min(n, (uint64_t)(c + 1) * C);
-    const uint64_t i0 = min(cend, (uint64_t)c * C + threadIdx.x * run);
-    const uint64_t i1 = min(cend, i0 + run);
-    uint64_t vals[RUN];
-    const uint32_t bits = run_bits<RUN>(in, w, lc_lds, i0, i1, vals);
-    uint32_t total;
-    const uint32_t start = block_incl_scan(bits, sm, &total) - bits;
-    const uint32_t nw = (total + 31u) >> 5;
-    // a chunk beyond its slot would mean the code and the data disagree:
-    // flagged, never written
-    const bool fits = nw <= slot;
-    if (threadIdx.x == 0) {
-      if (!fits) atomicOr(err, kErrCorrupt);
-      cnta[c] = nw;
-      words += nw;
-    }
-    for (uint32_t j = threadIdx.x; j < nw && fits; j += kThreads) buf[j] = 0;
-    __syncthreads();
-    if (bits && fits) {
-      BitSink sk{0ull, (int)(start & 31u), start >> 5, buf};
-#pragma unroll
-      for (int j = 0; j < RUN; j++) {
-        if (i0 + j >= i1) break;
-        const uint64_t v = vals[j];
-        int ex;
-        const int sym = symbol_of(v, &ex);
-        const uint32_t lc = code_of(w, lc_lds, sym);
-        sk.push(lc & 0xFFFFu, (int)(lc >> 16));
-        if (ex) {
-          const uint64_t x = v - (1ull << ex);
-          if (ex > 32) {
-            sk.push(x >> 32, ex - 32);
-            sk.push(x & 0xFFFFFFFFull, 32);
-          } else {
-            sk.push(x, ex);
-          }
-        }
-      }
-      sk.flush();
-    }
-    __syncthreads();
-    uint32_t* dst = pay + (uint64_t)c * slot;
-    for (uint32_t j = threadIdx.x; j < nw && fits; j += kThreads) dst[j] = buf[j];
-    __syncthreads();
-  }
+  if (e.in.is64)
+    pack_chunks<RUN, uint64_t>(e.in.v, n, chunk_log2, lb, nb, lc, buf, sm, cnta, pay, slot64,
+                               &words, err);
+  else
+    pack_chunks<RUN, uint32_t>(e.in.v, n, chunk_log2, lb, nb, lc, buf, sm, cnta, pay, slot32,
+                               &words, err);
   if (threadIdx.x == 0 && words) atomicAdd(&w.huff_words, words);
 }
 
