@@ -937,12 +937,10 @@ __global__ __launch_bounds__(kHT) void k_layout(ArrWork* W, EncRec* recs, int R,
 }
 
 // ------------------------------------------------------------------ packing
-__global__ __launch_bounds__(kThreads) void k_pack_fixed(const EncArr* E, const ArrWork* W,
-                                                         const EncRec* recs, const uint32_t* pre,
-                                                         int NA, uint8_t* out,
-                                                         const uint32_t* err) {
-  const uint32_t a = array_of_block(pre, NA, blockIdx.x);
-  const uint32_t lb = blockIdx.x - pre[a], nb = pre[a + 1] - pre[a];
+// Workgroup lb of the nb that pack fixed-length array a.
+__device__ inline void pack_fixed_block(const EncArr* E, const ArrWork* W, const EncRec* recs,
+                                        uint32_t a, uint32_t lb, uint32_t nb, uint8_t* out,
+                                        const uint32_t* err) {
   const ArrWork& w = W[a];
   if (w.coder != 0 || w.w == 0 || (*err & kErrCapacity)) return;
   const ArrIn in = E[a].in;
@@ -1115,16 +1113,12 @@ __global__ __launch_bounds__(kThreads) void k_pack_huff(const EncArr* E, ArrWork
 // 256 chunks at a time, scanning their counts and copying their words as one
 // flat range (a word finds its chunk by binary search over the tile's
 // offsets), so that loads of different chunks overlap.
-__global__ __launch_bounds__(kThreads) void k_copy_huff(const EncArr* E, const ArrWork* W,
-                                                        const EncRec* recs, const uint32_t* pre,
-                                                        int NA, const uint32_t* cnt,
-                                                        const uint32_t* stage, uint32_t slot32,
-                                                        uint32_t slot64, uint8_t* out,
-                                                        const uint32_t* err) {
+__device__ inline void copy_huff_block(const EncArr* E, const ArrWork* W, const EncRec* recs,
+                                       uint32_t a, uint32_t lb, uint32_t nb, const uint32_t* cnt,
+                                       const uint32_t* stage, uint32_t slot32, uint32_t slot64,
+                                       uint8_t* out, const uint32_t* err) {
   __shared__ unsigned long long sm[kThreads / kWave + 1];
   __shared__ uint32_t c_end[kThreads];  // inclusive word ends inside the tile
-  const uint32_t a = array_of_block(pre, NA, blockIdx.x);
-  const uint32_t lb = blockIdx.x - pre[a], nb = pre[a + 1] - pre[a];
   const ArrWork& w = W[a];
   if (w.coder != 1 || (*err & (kErrCapacity | kErrCorrupt))) return;
   const EncArr& e = E[a];
@@ -1177,6 +1171,27 @@ __global__ __launch_bounds__(kThreads) void k_copy_huff(const EncArr* E, const A
     }
     base += tot;
     __syncthreads();
+  }
+}
+
+// The arrays' payloads once the layout has placed them: workgroups below
+// fixed_blocks pack fixed-length arrays, the rest copy Huffman arrays.
+__global__ __launch_bounds__(kThreads) void k_emit(const EncArr* E, const ArrWork* W,
+                                                   const EncRec* recs, const uint32_t* pre_fixed,
+                                                   uint32_t fixed_blocks, const uint32_t* pre_copy,
+                                                   int NA, const uint32_t* cnt,
+                                                   const uint32_t* stage, uint32_t slot32,
+                                                   uint32_t slot64, uint8_t* out,
+                                                   const uint32_t* err) {
+  if (blockIdx.x < fixed_blocks) {
+    const uint32_t a = array_of_block(pre_fixed, NA, blockIdx.x);
+    pack_fixed_block(E, W, recs, a, blockIdx.x - pre_fixed[a], pre_fixed[a + 1] - pre_fixed[a],
+                     out, err);
+  } else {
+    const uint32_t b = blockIdx.x - fixed_blocks;
+    const uint32_t a = array_of_block(pre_copy, NA, b);
+    copy_huff_block(E, W, recs, a, b - pre_copy[a], pre_copy[a + 1] - pre_copy[a], cnt, stage,
+                    slot32, slot64, out, err);
   }
 }
 
@@ -1300,12 +1315,16 @@ __device__ inline bool store_value(const DecArr& d, uint64_t i, uint64_t v) {
   return true;
 }
 
-// One thread per chunk; the array's lookup table is staged in LDS.  32-bit
-// outputs go through an LDS tile: every round each thread decodes kRound
-// symbols of its chunk, then the workgroup writes the 256 x kRound tile back as
-// 64-byte segments (one cache-line half per 16 lanes) instead of 64 scattered
-// words per store.
+// One thread per chunk; the array's lookup table is staged in LDS with 16-bit
+// entries (length << 12 | symbol, 0 for a length-class symbol or an invalid
+// window, which then take the 32-bit table in global memory), so the LDS a
+// workgroup needs leaves room for more of them per CU.  32-bit outputs go
+// through an LDS tile: every round each thread decodes kRound symbols of its
+// chunk, then the workgroup writes the 256 x kRound tile back as 64-byte
+// segments (one cache-line half per 16 lanes) instead of 64 scattered words
+// per store.
 constexpr int kRound = 16;
+static_assert(kRound == 16, "the tile write-back moves one round of a chunk as 16 lanes x 4 bytes");
 
 // MSB-first reader over one chunk's words, double-buffered in registers: the
 // words being consumed (cur, arrived) and the next block of kRdWords words
@@ -1315,23 +1334,30 @@ constexpr int kRound = 16;
 // indices, no scratch).
 constexpr int kRdWords = 8;
 
+// The payload is read through global (not flat) loads, unconditionally (past
+// the chunk's end they read on, clamped to the payload's last word): flat
+// accesses would also count as LDS traffic, so every table lookup would wait
+// for the block in flight, and a conditional load is waited for at once.
+typedef const __attribute__((address_space(1))) uint32_t* GWords;
+
 struct BitReader {
   uint64_t buf;
   int nb;
   int ci;              // next word of cur to append
-  uint64_t wp, wend;   // next word to load into nxt, end of the chunk
+  uint64_t wp, last;   // next word to load into nxt, the payload's last word
   uint64_t rem;        // words not yet appended
   uint32_t cur[kRdWords], nxt[kRdWords];
-  const uint32_t* payload;
+  GWords payload;
   __device__ inline void load_block(uint32_t* dst) {
 #pragma unroll
-    for (int j = 0; j < kRdWords; j++) dst[j] = wp + j < wend ? payload[wp + j] : 0u;
+    for (int j = 0; j < kRdWords; j++) dst[j] = payload[min(wp + j, last)];
     wp += kRdWords;
   }
-  __device__ inline void start(const uint32_t* p, uint64_t beg, uint64_t end) {
+  // Words [beg, end) of a payload of `words` >= 1 words.
+  __device__ inline void start(GWords p, uint64_t words, uint64_t beg, uint64_t end) {
     payload = p;
+    last = words - 1;
     wp = beg;
-    wend = end;
     rem = end - beg;
     buf = 0;
     nb = 0;
@@ -1374,10 +1400,13 @@ __device__ inline bool read_extra(BitReader& r, int eb, uint64_t* x) {
   return true;
 }
 
+typedef __attribute__((address_space(1))) uint64_t* GOut64;
+typedef __attribute__((address_space(1))) uint32_t* GOut32;
+
 template <int MODE>
 __device__ inline void put_value(const DecArr& d, uint32_t* tile_slot, uint64_t i, uint64_t v) {
-  if (MODE == 0) reinterpret_cast<uint64_t*>(d.out)[i] = v;
-  else if (MODE == 1) reinterpret_cast<uint64_t*>(d.out)[i] = (uint64_t)unzigzag64(v);
+  if (MODE == 0) ((GOut64)d.out)[i] = v;
+  else if (MODE == 1) ((GOut64)d.out)[i] = (uint64_t)unzigzag64(v);
   else if (MODE == 2) *tile_slot = (uint32_t)v;
   else *tile_slot = (uint32_t)(int32_t)unzigzag64(v);
 }
@@ -1386,11 +1415,15 @@ __device__ inline void put_value(const DecArr& d, uint32_t* tile_slot, uint64_t 
 // A refill always leaves at least 33 bits, so one test per symbol suffices for
 // the code itself (at most 13 bits).
 template <int MODE>
-__device__ inline bool decode_round(BitReader& r, const uint32_t* lut, int L, const DecArr& d,
-                                    uint64_t i0, int cnt, uint32_t* tile_row) {
+__device__ inline bool decode_round(BitReader& r, const uint16_t* lut, const uint32_t* glut,
+                                    int L, const DecArr& d, uint64_t i0, int cnt,
+                                    uint32_t* tile_row) {
   for (int j = 0; j < cnt; j++) {
     if (r.nb <= 32) r.refill();
-    const uint32_t e = lut[(uint32_t)(r.buf >> (64 - L))];
+    const uint32_t win = (uint32_t)(r.buf >> (64 - L));
+    const uint32_t e16 = lut[win];
+    uint32_t e = ((e16 >> 12) << 16) | (e16 & 0xFFFu);
+    if (e16 == 0) e = glut[win];
     const int l = (int)(e >> 16);
     if (l == 0 || l > r.nb) return false;
     const uint32_t sym = e & 0xFFFFu;
@@ -1410,15 +1443,20 @@ __device__ inline bool decode_round(BitReader& r, const uint32_t* lut, int L, co
 }
 
 template <int MODE>
-__device__ inline void decode_chunks(const DecArr& d, const uint32_t* lut, int L,
-                                     uint64_t c0, int chunk_log2, uint32_t* tile, uint32_t* err) {
+__device__ inline void decode_chunks(const DecArr& d, const uint16_t* lut, const uint32_t* glut,
+                                     int L, uint64_t c0, int chunk_log2, uint32_t* tile,
+                                     uint32_t* err) {
   const uint64_t C = 1ull << chunk_log2;
   const uint64_t nchunks = (d.n + C - 1) >> chunk_log2;
   const uint64_t c = c0 + threadIdx.x;
-  const uint32_t* offs = reinterpret_cast<const uint32_t*>(d.data) + d.used;
+  const GWords offs = (GWords)d.data + d.used;
   const uint64_t payload_words = d.nbytes / 4 - d.used - nchunks;
+  if (payload_words == 0) {  // n >= 1 symbols take at least one bit
+    if (threadIdx.x == 0) atomicOr(err, kErrCorrupt);
+    return;
+  }
   BitReader r;
-  r.start(offs + nchunks, 0, 0);
+  r.start(offs + nchunks, payload_words, 0, 0);
   bool ok = c < nchunks;
   uint64_t cbeg = 0, cend = 0;
   if (ok) {
@@ -1427,7 +1465,7 @@ __device__ inline void decode_chunks(const DecArr& d, const uint32_t* lut, int L
       atomicOr(err, kErrCorrupt);
       ok = false;
     } else {
-      r.start(offs + nchunks, wbeg, wend);
+      r.start(offs + nchunks, payload_words, wbeg, wend);
     }
     cbeg = c * C;
     cend = min(d.n, cbeg + C);
@@ -1439,7 +1477,7 @@ __device__ inline void decode_chunks(const DecArr& d, const uint32_t* lut, int L
     const uint64_t i0 = cbeg + rd * kRound;
     if (ok && i0 < cend) {
       const int cnt = (int)min((uint64_t)kRound, cend - i0);
-      if (!decode_round<MODE>(r, lut, L, d, i0, cnt, row)) {
+      if (!decode_round<MODE>(r, lut, glut, L, d, i0, cnt, row)) {
         atomicOr(err, kErrCorrupt);
         ok = false;
       }
@@ -1452,37 +1490,43 @@ __device__ inline void decode_chunks(const DecArr& d, const uint32_t* lut, int L
       const uint64_t cc = c0 + seg;
       const uint64_t i = cc * C + rd * kRound + sub;
       if (cc < nchunks && i < min(d.n, (cc + 1) * C))
-        reinterpret_cast<uint32_t*>(d.out)[i] = tile[seg * (kRound + 1) + sub];
+        ((GOut32)d.out)[i] = tile[seg * (kRound + 1) + sub];
     }
     __syncthreads();
   }
 }
 
-// One thread per chunk; the array's lookup table is staged in LDS.  32-bit
-// outputs go through an LDS tile: every round each thread decodes kRound
-// symbols of its chunk, then the workgroup writes the 256 x kRound tile back as
-// 64-byte segments (one cache-line half per 16 lanes) instead of 64 scattered
-// words per store.
+// Dynamic LDS: the tile (kThreads x (kRound + 1) words), then the 16-bit
+// table of 2^lut_log2 entries (lut_log2: the longest code among the launch's
+// arrays).
 __global__ __launch_bounds__(kThreads) void k_decode_huff(const DecArr* arrs,
                                                           const uint32_t* prefix, int A,
                                                           int chunk_log2,
-                                                          const uint32_t* lut_all,
+                                                          const uint32_t* lut_all, int lut_log2,
                                                           uint32_t* err) {
-  __shared__ uint32_t lut[1u << kMaxLen];
-  __shared__ uint32_t tile[kThreads * (kRound + 1)];
+  extern __shared__ uint32_t dyn[];
+  uint32_t* tile = dyn;
+  uint16_t* lut = reinterpret_cast<uint16_t*>(dyn + kThreads * (kRound + 1));
   const uint32_t a = array_of_block(prefix, A, blockIdx.x);
   const DecArr d = arrs[a];
   if (d.coder != 1 || d.param < 1 || d.param > kMaxLen || (*err & kErrCorrupt)) return;
   const int L = d.param;
+  if (L > lut_log2) {
+    if (threadIdx.x == 0) atomicOr(err, kErrCorrupt);
+    return;
+  }
   const uint32_t* src = lut_all + (uint64_t)a * (1u << kMaxLen);
-  for (uint32_t i = threadIdx.x; i < (1u << L); i += kThreads) lut[i] = src[i];
+  for (uint32_t i = threadIdx.x; i < (1u << L); i += kThreads) {
+    const uint32_t e = src[i], sym = e & 0xFFFFu, l = e >> 16;
+    lut[i] = (uint16_t)(sym < (uint32_t)kDirect && l ? (l << 12) | sym : 0u);
+  }
   __syncthreads();
   const uint64_t c0 = (uint64_t)(blockIdx.x - prefix[a]) * kThreads;
   switch (d.mode) {
-    case 0: decode_chunks<0>(d, lut, L, c0, chunk_log2, tile, err); break;
-    case 1: decode_chunks<1>(d, lut, L, c0, chunk_log2, tile, err); break;
-    case 2: decode_chunks<2>(d, lut, L, c0, chunk_log2, tile, err); break;
-    default: decode_chunks<3>(d, lut, L, c0, chunk_log2, tile, err); break;
+    case 0: decode_chunks<0>(d, lut, src, L, c0, chunk_log2, tile, err); break;
+    case 1: decode_chunks<1>(d, lut, src, L, c0, chunk_log2, tile, err); break;
+    case 2: decode_chunks<2>(d, lut, src, L, c0, chunk_log2, tile, err); break;
+    default: decode_chunks<3>(d, lut, src, L, c0, chunk_log2, tile, err); break;
   }
 }
 
@@ -1580,11 +1624,10 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
     });
   }
   k_layout<<<1, kHT, 0, s>>>(work, L.recs, L.R, out, cap, offs, base, err);
-  LCP_TIMED("pack_fixed", L.values * 6ull, s,
-            k_pack_fixed<<<L.fixed_blocks, kThreads, 0, s>>>(L.arrs, work, L.recs, pre_fixed, NA,
-                                                             out, err));
-  k_copy_huff<<<L.copy_blocks, kThreads, 0, s>>>(L.arrs, work, L.recs, pre_copy, NA,
-                                                  X.chunk_words, X.stage, slot32, slot64, out, err);
+  LCP_TIMED("emit", L.values * 6ull, s,
+            k_emit<<<L.fixed_blocks + L.copy_blocks, kThreads, 0, s>>>(
+                L.arrs, work, L.recs, pre_fixed, L.fixed_blocks, pre_copy, NA, X.chunk_words,
+                X.stage, slot32, slot64, out, err));
 }
 
 uint32_t decode_blocks(const DecArr& d, int chunk_log2, bool huff) {
@@ -1599,13 +1642,17 @@ uint32_t decode_blocks(const DecArr& d, int chunk_log2, bool huff) {
 
 void launch_decode(const DecArr* arrs_dev, int A, const uint32_t* huff_prefix_dev,
                    uint32_t huff_blocks, const uint32_t* fixed_prefix_dev, uint32_t fixed_blocks,
-                   int chunk_log2, uint64_t bytes, uint32_t* lut, uint32_t* err, hipStream_t s) {
+                   int chunk_log2, int lut_log2, uint64_t bytes, uint32_t* lut, uint32_t* err,
+                   hipStream_t s) {
   if (A == 0) return;
   k_lut<<<A, kHT, 0, s>>>(arrs_dev, lut, err);
+  if (lut_log2 < 1) lut_log2 = 1;
+  if (lut_log2 > kMaxLen) lut_log2 = kMaxLen;
+  const size_t shm = (size_t)kThreads * (kRound + 1) * 4 + (((size_t)2 << lut_log2) + 3) / 4 * 4;
   if (huff_blocks)
     LCP_TIMED("decode_huff", bytes, s,
-              k_decode_huff<<<huff_blocks, kThreads, 0, s>>>(arrs_dev, huff_prefix_dev, A,
-                                                            chunk_log2, lut, err));
+              k_decode_huff<<<huff_blocks, kThreads, shm, s>>>(arrs_dev, huff_prefix_dev, A,
+                                                              chunk_log2, lut, lut_log2, err));
   if (fixed_blocks)
     LCP_TIMED("decode_fixed", bytes, s,
               k_decode_fixed<<<fixed_blocks, kThreads, 0, s>>>(arrs_dev, fixed_prefix_dev, A, err));

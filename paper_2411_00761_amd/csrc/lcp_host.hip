@@ -1032,17 +1032,21 @@ lcp_status decode_arrays(lcp_plan_s* P, int base, int A, int cl, uint64_t bytes,
   uint32_t* hp = P->prefix_host + 2 * base;
   uint32_t* fp = hp + A;
   uint32_t hb = 0, fb = 0;
+  int lut_log2 = 1;
   for (int a = 0; a < A; a++) {
+    const DecArr& d = P->arrtab_host[base + a];
     hp[a] = hb;
     fp[a] = fb;
-    hb += decode_blocks(P->arrtab_host[base + a], cl, true);
-    fb += decode_blocks(P->arrtab_host[base + a], cl, false);
+    hb += decode_blocks(d, cl, true);
+    fb += decode_blocks(d, cl, false);
+    if (d.coder == 1 && d.param > lut_log2) lut_log2 = d.param;
   }
   lcp_status st = upload(P->arrtab_host + base, P->arrtab_dev + base, sizeof(DecArr) * A, s);
   if (!st) st = upload(hp, P->prefix_dev + 2 * base, sizeof(uint32_t) * 2 * A, s);
   if (st) return st;
   launch_decode(P->arrtab_dev + base, A, P->prefix_dev + 2 * base, hb,
-                P->prefix_dev + 2 * base + A, fb, cl, bytes, P->lut + ((uint64_t)base << kMaxLen),
+                P->prefix_dev + 2 * base + A, fb, cl, lut_log2, bytes,
+                P->lut + ((uint64_t)base << kMaxLen),
                 P->err, s);
   return LCP_OK;
 }

@@ -291,8 +291,10 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
 uint32_t decode_blocks(const DecArr& d, int chunk_log2, bool huff);
 // Decode A arrays (descriptors in device memory).  *_prefix_dev[a] is the first
 // workgroup of array a in each launch (A entries); lut holds 2^13 entries per array.
+// lut_log2: the longest Huffman code among the arrays (sizes the LDS table).
 void launch_decode(const DecArr* arrs_dev, int A, const uint32_t* huff_prefix_dev,
                    uint32_t huff_blocks, const uint32_t* fixed_prefix_dev, uint32_t fixed_blocks,
-                   int chunk_log2, uint64_t bytes, uint32_t* lut, uint32_t* err, hipStream_t s);
+                   int chunk_log2, int lut_log2, uint64_t bytes, uint32_t* lut, uint32_t* err,
+                   hipStream_t s);
 
 }  // namespace lcp
