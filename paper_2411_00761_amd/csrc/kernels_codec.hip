@@ -1315,76 +1315,53 @@ __device__ inline bool store_value(const DecArr& d, uint64_t i, uint64_t v) {
   return true;
 }
 
-// One thread per chunk; the array's lookup table is staged in LDS with 16-bit
-// entries (length << 12 | symbol, 0 for a length-class symbol or an invalid
-// window, which then take the 32-bit table in global memory), so the LDS a
-// workgroup needs leaves room for more of them per CU.  32-bit outputs go
-// through an LDS tile: every round each thread decodes kRound symbols of its
-// chunk, then the workgroup writes the 256 x kRound tile back as 64-byte
-// segments (one cache-line half per 16 lanes) instead of 64 scattered words
-// per store.
+// One thread per chunk.  The array's lookup table is staged in LDS with 16-bit
+// entries (length << 12 | symbol; 0 for a length-class symbol or an invalid
+// window, which then take the 32-bit table in global memory).  Each thread
+// decodes its chunk in rounds of kRound symbols and reads its payload through
+// a ring of kRing words in LDS: every round every thread commits the K words
+// it loaded in the round before into its ring (if they are the next ones and
+// fit) and loads the following K, unconditionally, so those loads are waited
+// for one round later, and a refill of the bit buffer only reads LDS.  No
+// workgroup barrier follows the table fill: waves decode independently.  A
+// ring that runs dry (a round that needs more than K words) reads the next
+// word from global memory directly.  Payload reads and output stores use
+// global, not flat, addressing: flat accesses also count as LDS traffic, so
+// every table lookup would wait for them.
 constexpr int kRound = 16;
-static_assert(kRound == 16, "the tile write-back moves one round of a chunk as 16 lanes x 4 bytes");
-
-// MSB-first reader over one chunk's words, double-buffered in registers: the
-// words being consumed (cur, arrived) and the next block of kRdWords words
-// (nxt, in flight since the previous swap), so a load's latency is covered by
-// decoding a whole block (hundreds of bits) instead of one 32-bit refill.  The
-// word to append is picked by a select chain over cur (static register
-// indices, no scratch).
-constexpr int kRdWords = 8;
-
-// The payload is read through global (not flat) loads, unconditionally (past
-// the chunk's end they read on, clamped to the payload's last word): flat
-// accesses would also count as LDS traffic, so every table lookup would wait
-// for the block in flight, and a conditional load is waited for at once.
+constexpr int kRing = 16;
 typedef const __attribute__((address_space(1))) uint32_t* GWords;
+typedef __attribute__((address_space(1))) uint64_t* GOut64;
+typedef __attribute__((address_space(1))) uint32_t* GOut32;
+typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) U32x4* GOut128;
 
-struct BitReader {
+// One chunk's bits, MSB first: buf holds nb valid bits; words [rpos, wpos)
+// are in the ring; cw words in the chunk.
+struct RingReader {
   uint64_t buf;
   int nb;
-  int ci;              // next word of cur to append
-  uint64_t wp, last;   // next word to load into nxt, the payload's last word
-  uint64_t rem;        // words not yet appended
-  uint32_t cur[kRdWords], nxt[kRdWords];
-  GWords payload;
-  __device__ inline void load_block(uint32_t* dst) {
-#pragma unroll
-    for (int j = 0; j < kRdWords; j++) dst[j] = payload[min(wp + j, last)];
-    wp += kRdWords;
-  }
-  // Words [beg, end) of a payload of `words` >= 1 words.
-  __device__ inline void start(GWords p, uint64_t words, uint64_t beg, uint64_t end) {
-    payload = p;
-    last = words - 1;
-    wp = beg;
-    rem = end - beg;
-    buf = 0;
-    nb = 0;
-    ci = 0;
-    load_block(cur);
-    load_block(nxt);
-  }
+  uint32_t rpos, wpos, cw;
+  GWords pay;          // the chunk's first word
+  uint32_t* ring;      // slot s of this thread at ring[s * kThreads]
   __device__ inline void refill() {
-    while (nb <= 32 && rem > 0) {
-      uint32_t w = cur[0];
-#pragma unroll
-      for (int j = 1; j < kRdWords; j++) w = ci == j ? cur[j] : w;
+    if (nb <= 32 && rpos < cw) {
+      uint32_t w;
+      if (rpos < wpos) {
+        w = ring[(rpos & (kRing - 1)) * kThreads];
+      } else {
+        w = pay[rpos];
+        wpos = rpos + 1;
+      }
       buf |= (uint64_t)w << (32 - nb);
       nb += 32;
-      rem--;
-      if (++ci == kRdWords) {
-#pragma unroll
-        for (int j = 0; j < kRdWords; j++) cur[j] = nxt[j];
-        load_block(nxt);
-        ci = 0;
-      }
+      rpos++;
     }
   }
 };
 
 // Raw bits that follow a length-class symbol (rare): up to 63 bits.
-__device__ inline bool read_extra(BitReader& r, int eb, uint64_t* x) {
+__device__ inline bool read_extra(RingReader& r, int eb, uint64_t* x) {
   uint64_t v = 0;
   int rem = eb;
   while (rem > 0) {
@@ -1400,118 +1377,161 @@ __device__ inline bool read_extra(BitReader& r, int eb, uint64_t* x) {
   return true;
 }
 
-typedef __attribute__((address_space(1))) uint64_t* GOut64;
-typedef __attribute__((address_space(1))) uint32_t* GOut32;
-
-template <int MODE>
-__device__ inline void put_value(const DecArr& d, uint32_t* tile_slot, uint64_t i, uint64_t v) {
-  if (MODE == 0) ((GOut64)d.out)[i] = v;
-  else if (MODE == 1) ((GOut64)d.out)[i] = (uint64_t)unzigzag64(v);
-  else if (MODE == 2) *tile_slot = (uint32_t)v;
-  else *tile_slot = (uint32_t)(int32_t)unzigzag64(v);
-}
-
-// Decodes up to kRound symbols of one chunk; returns false on a malformed stream.
-// A refill always leaves at least 33 bits, so one test per symbol suffices for
-// the code itself (at most 13 bits).
-template <int MODE>
-__device__ inline bool decode_round(BitReader& r, const uint16_t* lut, const uint32_t* glut,
-                                    int L, const DecArr& d, uint64_t i0, int cnt,
-                                    uint32_t* tile_row) {
-  for (int j = 0; j < cnt; j++) {
-    if (r.nb <= 32) r.refill();
-    const uint32_t win = (uint32_t)(r.buf >> (64 - L));
-    const uint32_t e16 = lut[win];
-    uint32_t e = ((e16 >> 12) << 16) | (e16 & 0xFFFu);
-    if (e16 == 0) e = glut[win];
-    const int l = (int)(e >> 16);
-    if (l == 0 || l > r.nb) return false;
-    const uint32_t sym = e & 0xFFFFu;
-    r.buf <<= l;
-    r.nb -= l;
-    uint64_t v = sym;
-    if (sym >= (uint32_t)kDirect) {
-      const int eb = (int)sym - kDirect + kFirstClassBits - 1;
-      uint64_t x;
-      if (!read_extra(r, eb, &x)) return false;
-      v = (1ull << eb) + x;
-    }
-    if (v >= d.limit) return false;
-    put_value<MODE>(d, tile_row + j, i0 + j, v);
+// One symbol; false on a malformed stream.  A refill leaves at least 33 bits
+// unless the chunk ends, so one test covers the code itself (at most 13 bits).
+__device__ inline bool decode_symbol(RingReader& r, const uint16_t* lut, const uint32_t* glut,
+                                     int L, const DecArr& d, uint64_t* out) {
+  if (r.nb <= 32) r.refill();
+  const uint32_t win = (uint32_t)(r.buf >> (64 - L));
+  const uint32_t e16 = lut[win];
+  uint32_t e = ((e16 >> 12) << 16) | (e16 & 0xFFFu);
+  if (e16 == 0) e = glut[win];
+  const int l = (int)(e >> 16);
+  if (l == 0 || l > r.nb) return false;
+  const uint32_t sym = e & 0xFFFFu;
+  r.buf <<= l;
+  r.nb -= l;
+  uint64_t v = sym;
+  if (sym >= (uint32_t)kDirect) {
+    const int eb = (int)sym - kDirect + kFirstClassBits - 1;
+    uint64_t x;
+    if (!read_extra(r, eb, &x)) return false;
+    v = (1ull << eb) + x;
   }
+  if (v >= d.limit) return false;
+  *out = v;
   return true;
 }
 
 template <int MODE>
-__device__ inline void decode_chunks(const DecArr& d, const uint16_t* lut, const uint32_t* glut,
-                                     int L, uint64_t c0, int chunk_log2, uint32_t* tile,
-                                     uint32_t* err) {
+__device__ inline uint64_t out_value(uint64_t v) {
+  return (MODE == 1 || MODE == 3) ? (uint64_t)unzigzag64(v) : v;
+}
+
+template <int MODE, int K>
+__device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const uint32_t* glut,
+                                    int L, uint64_t c, int chunk_log2, uint32_t* ring,
+                                    uint32_t* err) {
   const uint64_t C = 1ull << chunk_log2;
   const uint64_t nchunks = (d.n + C - 1) >> chunk_log2;
-  const uint64_t c = c0 + threadIdx.x;
   const GWords offs = (GWords)d.data + d.used;
   const uint64_t payload_words = d.nbytes / 4 - d.used - nchunks;
-  if (payload_words == 0) {  // n >= 1 symbols take at least one bit
-    if (threadIdx.x == 0) atomicOr(err, kErrCorrupt);
+  const uint64_t wbeg = c ? offs[c - 1] : 0, wend = offs[c];
+  // a chunk holds at least one symbol, so at least one word
+  if (wbeg >= wend || wend > payload_words || (c == nchunks - 1 && wend != payload_words)) {
+    atomicOr(err, kErrCorrupt);
     return;
   }
-  BitReader r;
-  r.start(offs + nchunks, payload_words, 0, 0);
-  bool ok = c < nchunks;
-  uint64_t cbeg = 0, cend = 0;
-  if (ok) {
-    const uint64_t wbeg = c ? offs[c - 1] : 0, wend = offs[c];
-    if (wbeg > wend || wend > payload_words || (c == nchunks - 1 && wend != payload_words)) {
-      atomicOr(err, kErrCorrupt);
-      ok = false;
-    } else {
-      r.start(offs + nchunks, payload_words, wbeg, wend);
-    }
-    cbeg = c * C;
-    cend = min(d.n, cbeg + C);
+  RingReader r;
+  r.pay = offs + nchunks + wbeg;
+  r.cw = (uint32_t)(wend - wbeg);
+  r.ring = ring + threadIdx.x;
+  r.buf = 0;
+  r.nb = 0;
+  r.rpos = 0;
+  const uint64_t last = payload_words - 1 - wbeg;  // loads past the chunk stay in the payload
+  {
+    uint32_t w0[kRing];
+#pragma unroll
+    for (int j = 0; j < kRing; j++) w0[j] = r.pay[min((uint64_t)j, last)];
+#pragma unroll
+    for (int j = 0; j < kRing; j++) r.ring[j * kThreads] = w0[j];
   }
-  constexpr bool kWide = MODE < 2;  // 64-bit outputs (block ids / counts): stored directly
-  const uint64_t rounds = (min(C, d.n - min(d.n, c0 * C)) + kRound - 1) / kRound;
-  uint32_t* row = tile + threadIdx.x * (kRound + 1);
-  for (uint64_t rd = 0; rd < rounds; rd++) {
-    const uint64_t i0 = cbeg + rd * kRound;
-    if (ok && i0 < cend) {
-      const int cnt = (int)min((uint64_t)kRound, cend - i0);
-      if (!decode_round<MODE>(r, lut, glut, L, d, i0, cnt, row)) {
-        atomicOr(err, kErrCorrupt);
-        ok = false;
+  r.wpos = min((uint32_t)kRing, r.cw);
+  uint32_t pf[K];
+  uint32_t pfpos = r.wpos;
+#pragma unroll
+  for (int j = 0; j < K; j++) pf[j] = r.pay[min((uint64_t)pfpos + j, last)];
+  const uint64_t cbeg = c * C, cend = min(d.n, cbeg + C);
+  const bool vec = MODE >= 2 && (reinterpret_cast<uintptr_t>(d.out) & 15) == 0;
+  for (uint64_t i0 = cbeg; i0 < cend; i0 += kRound) {
+    if (pfpos == r.wpos && r.wpos < r.cw && r.wpos + K <= r.rpos + kRing) {
+#pragma unroll
+      for (int j = 0; j < K; j++) r.ring[((r.wpos + j) & (kRing - 1)) * kThreads] = pf[j];
+      r.wpos = min(r.wpos + K, r.cw);
+    }
+    pfpos = r.wpos;
+#pragma unroll
+    for (int j = 0; j < K; j++) pf[j] = r.pay[min((uint64_t)pfpos + j, last)];
+    const int cnt = (int)min((uint64_t)kRound, cend - i0);
+    if (MODE < 2) {
+      for (int j = 0; j < cnt; j++) {
+        uint64_t v;
+        if (!decode_symbol(r, lut, glut, L, d, &v)) {
+          atomicOr(err, kErrCorrupt);
+          return;
+        }
+        ((GOut64)d.out)[i0 + j] = out_value<MODE>(v);
+      }
+    } else {
+      uint32_t vals[kRound];
+#pragma unroll
+      for (int j = 0; j < kRound; j++) {
+        vals[j] = 0;
+        if (j < cnt) {
+          uint64_t v;
+          if (!decode_symbol(r, lut, glut, L, d, &v)) {
+            atomicOr(err, kErrCorrupt);
+            return;
+          }
+          vals[j] = (uint32_t)out_value<MODE>(v);
+        }
+      }
+      if (vec && cnt == kRound) {
+        GOut128 o = (GOut128)((GOut32)d.out + i0);
+#pragma unroll
+        for (int q = 0; q < kRound / 4; q++)
+          o[q] = U32x4{vals[4 * q], vals[4 * q + 1], vals[4 * q + 2], vals[4 * q + 3]};
+      } else {
+#pragma unroll
+        for (int j = 0; j < kRound; j++)
+          if (j < cnt) ((GOut32)d.out)[i0 + j] = vals[j];
       }
     }
-    if (kWide) continue;
-    __syncthreads();
-    // 16 lanes per 64-byte segment: segment = one chunk's kRound values this round
-    const int sub = lane_id() & 15;
-    for (int seg = wave_id() * 64 + (lane_id() >> 4); seg < wave_id() * 64 + 64; seg += 4) {
-      const uint64_t cc = c0 + seg;
-      const uint64_t i = cc * C + rd * kRound + sub;
-      if (cc < nchunks && i < min(d.n, (cc + 1) * C))
-        ((GOut32)d.out)[i] = tile[seg * (kRound + 1) + sub];
-    }
-    __syncthreads();
   }
 }
 
-// Dynamic LDS: the tile (kThreads x (kRound + 1) words), then the 16-bit
-// table of 2^lut_log2 entries (lut_log2: the longest code among the launch's
-// arrays).
+// Words to load per round: about one and a half times the array's average
+// (payload words per kRound symbols), rounded up to a power of two, at most 8.
+__device__ inline int ring_words(const DecArr& d, uint64_t nchunks) {
+  const uint64_t pw = d.nbytes / 4 - d.used - nchunks;
+  const uint64_t need = (pw * kRound * 3 / 2 + d.n - 1) / d.n + 1;
+  return need <= 1 ? 1 : need <= 2 ? 2 : need <= 4 ? 4 : 8;
+}
+
+template <int MODE>
+__device__ inline void decode_chunk_k(int K, const DecArr& d, const uint16_t* lut,
+                                      const uint32_t* glut, int L, uint64_t c, int chunk_log2,
+                                      uint32_t* ring, uint32_t* err) {
+  switch (K) {
+    case 1: decode_chunk<MODE, 1>(d, lut, glut, L, c, chunk_log2, ring, err); break;
+    case 2: decode_chunk<MODE, 2>(d, lut, glut, L, c, chunk_log2, ring, err); break;
+    case 4: decode_chunk<MODE, 4>(d, lut, glut, L, c, chunk_log2, ring, err); break;
+    default: decode_chunk<MODE, 8>(d, lut, glut, L, c, chunk_log2, ring, err); break;
+  }
+}
+
+// Dynamic LDS: the rings (kRing x kThreads words), then the 16-bit table of
+// 2^lut_log2 entries (lut_log2: the longest code among the launch's arrays).
 __global__ __launch_bounds__(kThreads) void k_decode_huff(const DecArr* arrs,
                                                           const uint32_t* prefix, int A,
                                                           int chunk_log2,
                                                           const uint32_t* lut_all, int lut_log2,
                                                           uint32_t* err) {
   extern __shared__ uint32_t dyn[];
-  uint32_t* tile = dyn;
-  uint16_t* lut = reinterpret_cast<uint16_t*>(dyn + kThreads * (kRound + 1));
+  uint32_t* ring = dyn;
+  uint16_t* lut = reinterpret_cast<uint16_t*>(dyn + kThreads * kRing);
   const uint32_t a = array_of_block(prefix, A, blockIdx.x);
   const DecArr d = arrs[a];
   if (d.coder != 1 || d.param < 1 || d.param > kMaxLen || (*err & kErrCorrupt)) return;
   const int L = d.param;
   if (L > lut_log2) {
+    if (threadIdx.x == 0) atomicOr(err, kErrCorrupt);
+    return;
+  }
+  const uint64_t C = 1ull << chunk_log2;
+  const uint64_t nchunks = (d.n + C - 1) >> chunk_log2;
+  if (d.nbytes / 4 < (uint64_t)d.used + nchunks + 1) {  // no payload word
     if (threadIdx.x == 0) atomicOr(err, kErrCorrupt);
     return;
   }
@@ -1521,12 +1541,14 @@ __global__ __launch_bounds__(kThreads) void k_decode_huff(const DecArr* arrs,
     lut[i] = (uint16_t)(sym < (uint32_t)kDirect && l ? (l << 12) | sym : 0u);
   }
   __syncthreads();
-  const uint64_t c0 = (uint64_t)(blockIdx.x - prefix[a]) * kThreads;
+  const uint64_t c = (uint64_t)(blockIdx.x - prefix[a]) * kThreads + threadIdx.x;
+  if (c >= nchunks) return;
+  const int K = ring_words(d, nchunks);
   switch (d.mode) {
-    case 0: decode_chunks<0>(d, lut, src, L, c0, chunk_log2, tile, err); break;
-    case 1: decode_chunks<1>(d, lut, src, L, c0, chunk_log2, tile, err); break;
-    case 2: decode_chunks<2>(d, lut, src, L, c0, chunk_log2, tile, err); break;
-    default: decode_chunks<3>(d, lut, src, L, c0, chunk_log2, tile, err); break;
+    case 0: decode_chunk_k<0>(K, d, lut, src, L, c, chunk_log2, ring, err); break;
+    case 1: decode_chunk_k<1>(K, d, lut, src, L, c, chunk_log2, ring, err); break;
+    case 2: decode_chunk_k<2>(K, d, lut, src, L, c, chunk_log2, ring, err); break;
+    default: decode_chunk_k<3>(K, d, lut, src, L, c, chunk_log2, ring, err); break;
   }
 }
 
@@ -1648,7 +1670,7 @@ void launch_decode(const DecArr* arrs_dev, int A, const uint32_t* huff_prefix_de
   k_lut<<<A, kHT, 0, s>>>(arrs_dev, lut, err);
   if (lut_log2 < 1) lut_log2 = 1;
   if (lut_log2 > kMaxLen) lut_log2 = kMaxLen;
-  const size_t shm = (size_t)kThreads * (kRound + 1) * 4 + (((size_t)2 << lut_log2) + 3) / 4 * 4;
+  const size_t shm = (size_t)kThreads * kRing * 4 + (((size_t)2 << lut_log2) + 3) / 4 * 4;
   if (huff_blocks)
     LCP_TIMED("decode_huff", bytes, s,
               k_decode_huff<<<huff_blocks, kThreads, shm, s>>>(arrs_dev, huff_prefix_dev, A,
