@@ -811,14 +811,18 @@ __device__ inline void put64(uint8_t* base, uint64_t off, uint64_t v) {
 }
 
 // Chooses each array's coder (the shorter; a tie keeps fixed length), places
-// the arrays, sizes the records and places them back to back, then writes
-// each header, grid and directory that fits in the output.  Records are taken
-// kLayRecs at a time: thread j < kLayRecs reads record j's header, thread
-// (j, a) = (t / kMaxArrays, t % kMaxArrays) reads and decides array a of
-// record j, record threads turn the array sizes into offsets, and a workgroup
-// scan of the record sizes places the records.  Each phase is one round of
-// independent loads.  Every record size is a multiple of 4 bytes.
-constexpr int kLayRecs = kHT / kMaxArrays;
+// the arrays, sizes the records and places them back to back (from *base_dev
+// when given), then writes each header, grid and directory that fits in the
+// output, with NT threads.
+// Records are taken NT / kMaxArrays at a time: thread j reads record j's
+// header, thread (j, a) = (t / kMaxArrays, t % kMaxArrays) reads and decides
+// array a of record j, record threads turn the array sizes into offsets, and a
+// workgroup scan of the record sizes places the records.  Each phase is one
+// round of independent loads.  Every record size is a multiple of 4 bytes.
+template <int NT>
+constexpr size_t layout_lds_bytes() {
+  return 8 * (NT / kWave + 1) + 8 * (NT / kMaxArrays) * (kMaxArrays + 2) + 12 * (NT / kMaxArrays);
+}
 
 __device__ inline void write_header(const RecHdr& h, uint64_t B, uint64_t size, uint8_t* out) {
   const uint64_t hdr = (uint64_t)kHdrBytes + 8ull * h.F + (uint64_t)kDirBytes * h.A;
@@ -843,15 +847,19 @@ __device__ inline void write_header(const RecHdr& h, uint64_t B, uint64_t size, 
   }
 }
 
-__global__ __launch_bounds__(kHT) void k_layout(ArrWork* W, EncRec* recs, int R, uint8_t* out,
-                                                uint64_t cap, unsigned long long* offs,
-                                                const unsigned long long* base_dev,
-                                                uint32_t* err) {
-  __shared__ unsigned long long sm[kHT / kWave + 1];
-  __shared__ uint32_t s_a0[kLayRecs];
-  __shared__ int s_A[kLayRecs], s_F[kLayRecs];
-  __shared__ unsigned long long s_nb[kLayRecs][kMaxArrays];  // bytes, then offsets
-  __shared__ unsigned long long s_roff[kLayRecs], s_size[kLayRecs];
+template <int NT>
+__device__ void layout_records(ArrWork* W, EncRec* recs, const EncRec& rec0, int R, uint8_t* out,
+                               uint64_t cap, unsigned long long* offs,
+                               const unsigned long long* base_dev, uint32_t* err, uint8_t* lds) {
+  constexpr int kLayRecs = NT / kMaxArrays;
+  unsigned long long* sm = reinterpret_cast<unsigned long long*>(lds);
+  unsigned long long(*s_nb)[kMaxArrays] =
+      reinterpret_cast<unsigned long long(*)[kMaxArrays]>(sm + NT / kWave + 1);  // bytes, then offsets
+  unsigned long long* s_roff = reinterpret_cast<unsigned long long*>(s_nb + kLayRecs);
+  unsigned long long* s_size = s_roff + kLayRecs;
+  uint32_t* s_a0 = reinterpret_cast<uint32_t*>(s_size + kLayRecs);
+  int* s_A = reinterpret_cast<int*>(s_a0 + kLayRecs);
+  int* s_F = s_A + kLayRecs;
   const int t = (int)threadIdx.x;
   const int j = t / kMaxArrays, a = t % kMaxArrays;
   unsigned long long carry = base_dev ? *base_dev : 0ull;
@@ -861,7 +869,7 @@ __global__ __launch_bounds__(kHT) void k_layout(ArrWork* W, EncRec* recs, int R,
     RecHdr h;
     uint64_t B = 0;
     if (hv) {
-      const EncRec& rc = recs[r];
+      const EncRec& rc = R == 1 ? rec0 : recs[r];  // a single record comes as an argument
       h = rc.h;
       s_a0[t] = rc.a0;
       s_A[t] = h.A;
@@ -1104,6 +1112,15 @@ __global__ __launch_bounds__(kThreads) void k_pack_huff(const EncArr* E, ArrWork
     pack_chunks<RUN, uint32_t>(e.in.v, n, chunk_log2, lb, nb, lc, buf, sm, cnta, pay, slot32,
                                &words, err);
   if (threadIdx.x == 0 && words) atomicAdd(&w.huff_words, words);
+}
+
+__global__ __launch_bounds__(kHT) void k_layout(ArrWork* W, EncRec* recs, const EncRec rec0,
+                                                int R, uint8_t* out, uint64_t cap,
+                                                unsigned long long* offs,
+                                                const unsigned long long* base_dev,
+                                                uint32_t* err) {
+  __shared__ __align__(8) uint8_t lds[layout_lds_bytes<kHT>()];
+  layout_records<kHT>(W, recs, rec0, R, out, cap, offs, base_dev, err, lds);
 }
 
 // Huffman arrays the layout kept: code table, chunk end offsets and the
@@ -1645,7 +1662,7 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
       }
     });
   }
-  k_layout<<<1, kHT, 0, s>>>(work, L.recs, L.R, out, cap, offs, base, err);
+  k_layout<<<1, kHT, 0, s>>>(work, L.recs, L.rec0, L.R, out, cap, offs, base, err);
   LCP_TIMED("emit", L.values * 6ull, s,
             k_emit<<<L.fixed_blocks + L.copy_blocks, kThreads, 0, s>>>(
                 L.arrs, work, L.recs, pre_fixed, L.fixed_blocks, pre_copy, NA, X.chunk_words,

@@ -136,6 +136,10 @@ struct lcp_plan_s {
   int32_t* dqpool[3] = {nullptr, nullptr, nullptr};
   RefState prev, anchor, dprev, danchor;
   RefState sr_state_tmp;  // reference state of the spatial candidate of the current frame
+  // the encoder array and prefix tables last uploaded (valid while the scratch
+  // stays bound)
+  std::vector<uint8_t> enc_cache;
+  bool enc_cache_ok = false;
   bool have_eb = false;
   double eb_f[kMaxF];
   uint64_t seq = 0;
@@ -434,11 +438,31 @@ lcp_status enc_launch(lcp_plan_s* P, EncBuild& B, uint8_t* out, uint64_t cap, bo
   L.fixed_blocks = f;
   L.copy_blocks = k;
   L.values = B.values;
-  lcp_status st = upload_group({{P->erec_host, P->erec_dev, sizeof(EncRec) * B.R},
-                                 {P->earr_host, P->earr_dev, sizeof(EncArr) * NA},
-                                 {P->epre_host, P->epre_dev, sizeof(uint32_t) * 4 * (NA + 1)}},
-                                s);
+  // A single record travels to the layout kernel as an argument; the array and
+  // prefix tables are not uploaded again while the device holds the same bytes
+  // (consecutive temporal frames of one size)
+  L.rec0 = P->erec_host[0];
+  const size_t arr_bytes = sizeof(EncArr) * NA, pre_bytes = sizeof(uint32_t) * 4 * (NA + 1);
+  const bool same = P->enc_cache_ok && P->enc_cache.size() == arr_bytes + pre_bytes &&
+                    !memcmp(P->enc_cache.data(), P->earr_host, arr_bytes) &&
+                    !memcmp(P->enc_cache.data() + arr_bytes, P->epre_host, pre_bytes);
+  lcp_status st = LCP_OK;
+  if (B.R > 1 && same) st = upload(P->erec_host, P->erec_dev, sizeof(EncRec) * B.R, s);
+  else if (B.R > 1)
+    st = upload_group({{P->erec_host, P->erec_dev, sizeof(EncRec) * B.R},
+                       {P->earr_host, P->earr_dev, arr_bytes},
+                       {P->epre_host, P->epre_dev, pre_bytes}},
+                      s);
+  else if (!same)
+    st = upload_group({{P->earr_host, P->earr_dev, arr_bytes}, {P->epre_host, P->epre_dev, pre_bytes}},
+                      s);
   if (st) return st;
+  if (!same) {
+    P->enc_cache.resize(arr_bytes + pre_bytes);
+    memcpy(P->enc_cache.data(), P->earr_host, arr_bytes);
+    memcpy(P->enc_cache.data() + arr_bytes, P->epre_host, pre_bytes);
+    P->enc_cache_ok = true;
+  }
   EncScratch X;
   X.chunk_words = P->chunk_words;
   X.stage = P->stage;
@@ -1490,6 +1514,7 @@ void bind_scratch(lcp_plan_s* P, void* dev, void* host, hipStream_t s) {
   layout_scratch(P, D, H);
   D.place(dev);
   H.place(host);
+  P->enc_cache_ok = false;
   P->err = reinterpret_cast<uint32_t*>(P->ret_dev);
   P->offs_dev = P->ret_dev + 1;
   P->ext_dev = reinterpret_cast<uint32_t*>(P->ret_dev + 2 + P->RB);

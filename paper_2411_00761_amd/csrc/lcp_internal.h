@@ -265,7 +265,8 @@ constexpr int kHuffCandidates = 32;
 // the histograms are already in the spread copies.
 struct EncLaunch {
   const EncArr* arrs;
-  EncRec* recs;
+  EncRec* recs;     // the layout writes every record's size and offset here
+  EncRec rec0;      // the first record's header (the only one read when R == 1)
   const uint32_t* pre;
   int NA, R;
   uint32_t hist_blocks, chunk_blocks, fixed_blocks, copy_blocks;
