@@ -22,6 +22,10 @@ __device__ inline uint64_t arr_len(const ArrIn& a) {
   return a.n_dev ? min((uint64_t)*a.n_dev, a.n) : a.n;
 }
 __device__ inline uint64_t arr_load(const ArrIn& a, uint64_t i) {
+  if (a.esc) {
+    const uint32_t b = ((const uint8_t*)a.v)[i];
+    return b == 255u ? a.esc[i] : b;
+  }
   return a.is64 ? ((const uint64_t*)a.v)[i] : (uint64_t)((const uint32_t*)a.v)[i];
 }
 __device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
@@ -1008,15 +1012,22 @@ struct BitSink {
 // to cnt[c] and, summed per workgroup, into the array's total; where each
 // chunk lands in the record is settled by the copy once all are packed, so no
 // workgroup waits on another.
-// Packs chunk c from its values v (thread t's run) into the chunk's slot.
+// Packs chunk c from its values vin (thread t's run) into the chunk's slot;
+// with esc (byte arrays), a value 255 is replaced by esc at its index first.
 template <int RUN>
-__device__ inline void pack_chunk(uint32_t c, const uint64_t* v, uint64_t n, uint64_t C,
-                                  uint64_t run, const uint32_t* lc, uint32_t* buf, uint32_t* sm,
-                                  uint32_t* cnta, uint32_t* pay, uint32_t slot,
-                                  unsigned long long* words, uint32_t* err) {
+__device__ inline void pack_chunk(uint32_t c, const uint64_t* vin, const uint32_t* esc,
+                                  uint64_t n, uint64_t C, uint64_t run, const uint32_t* lc,
+                                  uint32_t* buf, uint32_t* sm, uint32_t* cnta, uint32_t* pay,
+                                  uint32_t slot, unsigned long long* words, uint32_t* err) {
   const uint64_t cend = min(n, (uint64_t)(c + 1) * C);
   const uint64_t i0 = min(cend, (uint64_t)c * C + threadIdx.x * run);
   const uint64_t i1 = min(cend, i0 + run);
+  uint64_t v[RUN];
+#pragma unroll
+  for (int j = 0; j < RUN; j++) {
+    v[j] = vin[j];
+    if (esc && v[j] == 255u && i0 + j < i1) v[j] = esc[i0 + j];
+  }
   uint32_t bits = 0;
 #pragma unroll
   for (int j = 0; j < RUN; j++) {
@@ -1067,9 +1078,9 @@ __device__ inline void pack_chunk(uint32_t c, const uint64_t* v, uint64_t n, uin
 // The workgroup's chunks lb, lb + nb, ... of an array of T, with two value
 // buffers: the next chunk's values are loaded while one is packed.
 template <int RUN, typename T>
-__device__ inline void pack_chunks(const void* v, uint64_t n, int chunk_log2, uint32_t lb,
-                                   uint32_t nb, const uint32_t* lc, uint32_t* buf, uint32_t* sm,
-                                   uint32_t* cnta, uint32_t* pay, uint32_t slot,
+__device__ inline void pack_chunks(const void* v, const uint32_t* esc, uint64_t n, int chunk_log2,
+                                   uint32_t lb, uint32_t nb, const uint32_t* lc, uint32_t* buf,
+                                   uint32_t* sm, uint32_t* cnta, uint32_t* pay, uint32_t slot,
                                    unsigned long long* words, uint32_t* err) {
   const uint64_t C = 1ull << chunk_log2;
   const uint32_t nchunks = (uint32_t)((n + C - 1) >> chunk_log2);
@@ -1078,10 +1089,10 @@ __device__ inline void pack_chunks(const void* v, uint64_t n, int chunk_log2, ui
   load_run<RUN, T>(v, n, chunk_log2, run, min(lb, nchunks - 1), va);
   for (uint32_t c = lb; c < nchunks; c += 2 * nb) {
     load_run<RUN, T>(v, n, chunk_log2, run, min(c + nb, nchunks - 1), vb);
-    pack_chunk<RUN>(c, va, n, C, run, lc, buf, sm, cnta, pay, slot, words, err);
+    pack_chunk<RUN>(c, va, esc, n, C, run, lc, buf, sm, cnta, pay, slot, words, err);
     if (c + nb >= nchunks) break;
     load_run<RUN, T>(v, n, chunk_log2, run, min(c + 2 * nb, nchunks - 1), va);
-    pack_chunk<RUN>(c + nb, vb, n, C, run, lc, buf, sm, cnta, pay, slot, words, err);
+    pack_chunk<RUN>(c + nb, vb, esc, n, C, run, lc, buf, sm, cnta, pay, slot, words, err);
   }
 }
 
@@ -1105,12 +1116,15 @@ __global__ __launch_bounds__(kThreads) void k_pack_huff(const EncArr* E, ArrWork
   uint32_t* cnta = cnt + e.cw0;
   uint32_t* pay = stage + e.stage0;
   unsigned long long words = 0;  // thread 0: this workgroup's share of the array
-  if (e.in.is64)
-    pack_chunks<RUN, uint64_t>(e.in.v, n, chunk_log2, lb, nb, lc, buf, sm, cnta, pay, slot64,
-                               &words, err);
+  if (e.in.esc)
+    pack_chunks<RUN, uint8_t>(e.in.v, e.in.esc, n, chunk_log2, lb, nb, lc, buf, sm, cnta, pay,
+                              slot32, &words, err);
+  else if (e.in.is64)
+    pack_chunks<RUN, uint64_t>(e.in.v, nullptr, n, chunk_log2, lb, nb, lc, buf, sm, cnta, pay,
+                               slot64, &words, err);
   else
-    pack_chunks<RUN, uint32_t>(e.in.v, n, chunk_log2, lb, nb, lc, buf, sm, cnta, pay, slot32,
-                               &words, err);
+    pack_chunks<RUN, uint32_t>(e.in.v, nullptr, n, chunk_log2, lb, nb, lc, buf, sm, cnta, pay,
+                               slot32, &words, err);
   if (threadIdx.x == 0 && words) atomicAdd(&w.huff_words, words);
 }
 

@@ -226,8 +226,9 @@ constexpr int kResPriv = 256;
 
 __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64_t n, GridDev g,
                                                       const uint32_t* perm_ref,
-                                                      const int32_t* q_ref, uint32_t* v_res,
-                                                      int32_t* q_new, uint32_t* err, int vec,
+                                                      const int32_t* q_ref, uint8_t* v8,
+                                                      uint32_t* v_res, int32_t* q_new,
+                                                      uint32_t* err, int vec,
                                                       uint32_t* hist_part,
                                                       unsigned long long* hist_max) {
   // per field and wave kResPriv private bins, sized by F at launch so that
@@ -269,7 +270,17 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
           qv[j] = (int32_t)q;
           rmax[f] = max(rmax[f], rv[j]);
         }
-        reinterpret_cast<uint4*>(v_res + (uint64_t)f * n)[s4] = make_uint4(rv[0], rv[1], rv[2], rv[3]);
+        if (v8) {
+          uint32_t bytes = 0;
+#pragma unroll
+          for (int j = 0; j < 4; j++) bytes |= min(rv[j], 255u) << (8 * j);
+          reinterpret_cast<uint32_t*>(v8 + (uint64_t)f * n)[s4] = bytes;
+#pragma unroll
+          for (int j = 0; j < 4; j++)
+            if (rv[j] >= 255u) v_res[(uint64_t)f * n + 4 * s4 + j] = rv[j];
+        } else {
+          reinterpret_cast<uint4*>(v_res + (uint64_t)f * n)[s4] = make_uint4(rv[0], rv[1], rv[2], rv[3]);
+        }
         reinterpret_cast<int4*>(q_new + (uint64_t)f * n)[s4] = make_int4(qv[0], qv[1], qv[2], qv[3]);
 #pragma unroll
         for (int j = 0; j < 4; j++) count(f, rv[j]);
@@ -282,7 +293,12 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
         int64_t q;
         t_code(x.p[f][i], g, f, &bad, &q);
         const uint32_t r = (uint32_t)zigzag64(q - (int64_t)q_ref[(uint64_t)f * n + s]);
-        v_res[(uint64_t)f * n + s] = r;
+        if (v8) {
+          v8[(uint64_t)f * n + s] = (uint8_t)min(r, 255u);
+          if (r >= 255u) v_res[(uint64_t)f * n + s] = r;
+        } else {
+          v_res[(uint64_t)f * n + s] = r;
+        }
         q_new[(uint64_t)f * n + s] = (int32_t)q;
         rmax[f] = max(rmax[f], r);
         count(f, r);
@@ -999,14 +1015,17 @@ void launch_s_recon_b(const uint32_t* blk, const uint32_t* corner, const uint32_
 inline bool al16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 
 void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
-                    const uint32_t* perm_ref, const int32_t* q_ref, uint32_t* v_res,
+                    const uint32_t* perm_ref, const int32_t* q_ref, uint8_t* v8, uint32_t* v_res,
                     int32_t* q_new, uint32_t* err, uint32_t* hist_part,
                     unsigned long long* hist_max, hipStream_t s) {
-  const int vec = (n % 4 == 0) && al16(perm_ref) && al16(q_ref) && al16(v_res) && al16(q_new);
-  LCP_TIMED("t_resid", n * (4 + 16ull * F), s,
+  const int vec = (n % 4 == 0) && al16(perm_ref) && al16(q_ref) && al16(v_res) && al16(q_new) &&
+                  (!v8 || al16(v8));
+  // algorithmic bytes: permutation, x and reference codes read; residuals
+  // (bytes, or u32) and new codes written
+  LCP_TIMED("t_resid", n * (4 + 12ull * F + (v8 ? 1ull : 4ull) * F), s,
             k_t_resid<<<grid_for(vec ? n / 4 : n, kThreads * 2, 2048), kThreads,
                         (size_t)F * (kThreads / kWave) * kResPriv * 4, s>>>(
-                x, F, n, g, perm_ref, q_ref, v_res, q_new, err, vec, hist_part, hist_max));
+                x, F, n, g, perm_ref, q_ref, v8, v_res, q_new, err, vec, hist_part, hist_max));
 }
 
 void launch_t_codes(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,

@@ -90,6 +90,7 @@ struct lcp_plan_s {
   // scratch (batch-wide arrays hold NB slots)
   uint64_t *keys0, *keys1, *ids, *v_id, *v_cnt, *prel;
   uint32_t *vals0, *vals1, *hist, *flags, *starts, *v_slot, *chunk_words, *lut, *corner;
+  uint8_t* v_byte;  // temporal residuals as bytes (multi-frame plans; escapes in v_slot)
   uint32_t* stage;  // Huffman payload staging, one slot per chunk
   uint64_t* scan_tmp;
   size_t scan_tmp_n;
@@ -665,7 +666,7 @@ lcp_status launch_t(lcp_plan_s* P, const float* const* x, uint64_t n, const RefS
                     unsigned long long* offs, const unsigned long long* base, hipStream_t s) {
   const int F = P->F;
   launch_t_resid(field_ptrs(x, F), F, n, t_grid(ref, F), P->ppool[ref.perm], P->qpool[ref.q],
-                 P->v_slot, q_new, err, P->hist_part, P->hist_max, s);
+                 P->v_byte, P->v_slot, q_new, err, P->hist_part, P->hist_max, s);
   EncBuild B;
   B.R = 1;
   EncRec& rc = P->erec_host[0];
@@ -675,8 +676,9 @@ lcp_status launch_t(lcp_plan_s* P, const float* const* x, uint64_t n, const RefS
   lcp_status st;
   // the residual kernel counts field f into spread copies f * kHistCopies ...
   for (int f = 0; f < F; f++)
-    if ((st = enc_add(P, B, ArrIn{P->v_slot + (uint64_t)f * n, 0, nullptr, n}, n, 0,
-                      f * kHistCopies, kHistCopies)))
+    if ((st = enc_add(P, B,
+                      ArrIn{P->v_byte + (uint64_t)f * n, 0, nullptr, n, P->v_slot + (uint64_t)f * n},
+                      n, 0, f * kHistCopies, kHistCopies)))
       return st;
   return enc_launch(P, B, out, cap, true, s, err, offs, base);
 }
@@ -1448,6 +1450,8 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   D.add(&P->flags, NB);
   D.add(&P->starts, NB);
   D.add(&P->v_slot, (uint64_t)F * NB);
+  if (P->p.multi_frame) D.add(&P->v_byte, (uint64_t)F * NB);
+  else P->v_byte = nullptr;
   D.add(&P->chunk_words, P->cw_cap);
   D.add(&P->stage, P->stage_cap);
   D.add(&P->lut, (uint64_t)(kMaxBatchArrays + 2 * kMaxBatchFrames) << kMaxLen);

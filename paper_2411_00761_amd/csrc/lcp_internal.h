@@ -33,6 +33,9 @@ struct ArrIn {
   int is64;
   const uint32_t* n_dev;
   uint64_t n;
+  // non-null: v holds one byte per value, and 255 means the value is esc[i]
+  // (temporal residuals, which are nearly all small)
+  const uint32_t* esc;
 };
 // Per-array coder workspace in device memory.
 struct ArrWork {
@@ -210,8 +213,10 @@ void launch_s_recon_b(const uint32_t* blk, const uint32_t* corner, const uint32_
 // coded on the reference grid.
 // The residual symbols of field f are also counted into array f's spread
 // histogram copies (hist_part / hist_max, as launch_encode expects them).
+// Residuals go to v8 as bytes (255: the value is in v_res, written for such
+// values only), or to v_res as u32 when v8 is null.
 void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
-                    const uint32_t* perm_ref, const int32_t* q_ref, uint32_t* v_res,
+                    const uint32_t* perm_ref, const int32_t* q_ref, uint8_t* v8, uint32_t* v_res,
                     int32_t* q_new, uint32_t* err, uint32_t* hist_part,
                     unsigned long long* hist_max, hipStream_t s);
 void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, uint64_t B,

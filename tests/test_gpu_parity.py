@@ -235,3 +235,27 @@ def test_temporal_residuals_need_the_length_limit(lcp):
         assert rec == want, f"frame {t}: " + diff_report(rec, want)
     P = fmt_ref.parse(want)
     assert P["mode"] == 1 and any(d["coder"] == 1 for d in P["dirs"])
+
+
+def test_temporal_residuals_above_a_byte_fixed_length(lcp):
+    """Residuals uniform in [-512, 512): zigzag values reach 1023, beyond what
+    one byte holds, and the flat distribution makes the fixed-length coder the
+    shorter one."""
+    n = 40000
+    rng = np.random.default_rng(91)
+    x0 = datagen.uniform_frame(n, hi=50.0, seed=92)
+    grids = O.grids_for(x0, O.EB_ABS, 1e-3)
+    x1 = np.empty_like(x0)
+    for f in range(3):
+        r = rng.integers(-512, 512, size=n)
+        x1[f] = O.reconstruct(O.quantize(x0[f], grids[f]) + r, grids[f])
+    ost = O.Stream(O.EB_ABS, 1e-3, batch_size=0, block_log2=6, max_n=n)
+    plan = lcp.Plan(1e-3, lcp.EB_ABS, multi_frame=True, batch_size=0, block_log2=6, max_particles=n)
+    for t, (x, m) in enumerate([(x0, O.METHOD_S), (x1, O.METHOD_T)]):
+        want, wused, _ = ost.compress(x, method=m)
+        out, offs, used, _ = plan.compress([torch.from_numpy(x).cuda()], methods=[m])
+        rec = out[offs[0]:offs[1]].cpu().numpy().tobytes()
+        assert used[0] == wused == m, t
+        assert rec == want, f"frame {t}: " + diff_report(rec, want)
+    P = fmt_ref.parse(want)
+    assert P["mode"] == 1 and all(d["coder"] == 0 and d["param"] >= 9 for d in P["dirs"])
