@@ -1028,12 +1028,18 @@ __device__ inline void pack_chunk(uint32_t c, const uint64_t* vin, const uint32_
     v[j] = vin[j];
     if (esc && v[j] == 255u && i0 + j < i1) v[j] = esc[i0 + j];
   }
-  uint32_t bits = 0;
+  // each value's code (code | length << 16) and raw extra bits, once
+  uint32_t cl[RUN];
+  int exb[RUN];
+  uint32_t bits = 0, extra = 0;
 #pragma unroll
   for (int j = 0; j < RUN; j++) {
-    int ex;
-    const int sym = symbol_of(v[j], &ex);
-    if (i0 + j < i1) bits += (lc[sym] >> 16) + (uint32_t)ex;
+    const int sym = symbol_of(v[j], &exb[j]);
+    const bool in = i0 + j < i1;
+    cl[j] = in ? lc[sym] : 0u;
+    exb[j] = in ? exb[j] : 0;
+    bits += (cl[j] >> 16) + (uint32_t)exb[j];
+    extra |= (uint32_t)exb[j];
   }
   uint32_t total;
   const uint32_t start = block_scan_lds(bits, sm, &total) - bits;
@@ -1049,25 +1055,35 @@ __device__ inline void pack_chunk(uint32_t c, const uint64_t* vin, const uint32_
   for (uint32_t j = threadIdx.x; j < nw && fits; j += kThreads) buf[j] = 0;
   lds_barrier();
   if (bits && fits) {
-    BitSink sk{0ull, (int)(start & 31u), start >> 5, buf};
+    if (bits <= 32 && !extra) {
+      // the run's codes fit one register: placed MSB first at bit `start`,
+      // they touch at most two words
+      uint64_t str = 0;
 #pragma unroll
-    for (int j = 0; j < RUN; j++) {
-      if (i0 + j >= i1) break;
-      int ex;
-      const int sym = symbol_of(v[j], &ex);
-      const uint32_t code = lc[sym];
-      sk.push(code & 0xFFFFu, (int)(code >> 16));
-      if (ex) {
-        const uint64_t x = v[j] - (1ull << ex);
-        if (ex > 32) {
-          sk.push(x >> 32, ex - 32);
-          sk.push(x & 0xFFFFFFFFull, 32);
-        } else {
-          sk.push(x, ex);
+      for (int j = 0; j < RUN; j++) str = (str << (cl[j] >> 16)) | (cl[j] & 0xFFFFu);
+      const uint64_t part = (str << (64 - bits)) >> (start & 31u);
+      const uint32_t w0 = start >> 5;
+      atomicOr(&buf[w0], (uint32_t)(part >> 32));
+      if ((uint32_t)part) atomicOr(&buf[w0 + 1], (uint32_t)part);
+    } else {
+      BitSink sk{0ull, (int)(start & 31u), start >> 5, buf};
+#pragma unroll
+      for (int j = 0; j < RUN; j++) {
+        if (i0 + j >= i1) break;
+        sk.push(cl[j] & 0xFFFFu, (int)(cl[j] >> 16));
+        const int ex = exb[j];
+        if (ex) {
+          const uint64_t x = v[j] - (1ull << ex);
+          if (ex > 32) {
+            sk.push(x >> 32, ex - 32);
+            sk.push(x & 0xFFFFFFFFull, 32);
+          } else {
+            sk.push(x, ex);
+          }
         }
       }
+      sk.flush();
     }
-    sk.flush();
   }
   lds_barrier();
   uint32_t* dst = pay + (uint64_t)c * slot;
