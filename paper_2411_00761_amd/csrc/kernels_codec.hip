@@ -1491,6 +1491,7 @@ __device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const 
   for (int j = 0; j < K; j++) pf[j] = r.pay[min((uint64_t)pfpos + j, last)];
   const uint64_t cbeg = c * C, cend = min(d.n, cbeg + C);
   const bool vec = MODE >= 2 && (reinterpret_cast<uintptr_t>(d.out) & 15) == 0;
+  const uint32_t lim = d.limit > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)d.limit;
   for (uint64_t i0 = cbeg; i0 < cend; i0 += kRound) {
     if (pfpos == r.wpos && r.wpos < r.cw && r.wpos + K <= r.rpos + kRing) {
 #pragma unroll
@@ -1512,16 +1513,51 @@ __device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const 
       }
     } else {
       uint32_t vals[kRound];
+      // A full round first without branches: the ring word is always read and
+      // appended where the buffer needs it; anything else (ring dry, escape
+      // entry, code longer than the bits left, value over the limit, a short
+      // round) marks the lane, which then starts the round again on the
+      // careful path.
+      const uint64_t buf0 = r.buf;
+      const int nb0 = r.nb;
+      const uint32_t rpos0 = r.rpos, wpos0 = r.wpos;
+      bool redo = cnt < kRound;
+      if (!redo) {
 #pragma unroll
-      for (int j = 0; j < kRound; j++) {
-        vals[j] = 0;
-        if (j < cnt) {
-          uint64_t v;
-          if (!decode_symbol(r, lut, glut, L, d, &v)) {
-            atomicOr(err, kErrCorrupt);
-            return;
+        for (int j = 0; j < kRound; j++) {
+          const bool need = r.nb <= 32 && r.rpos < r.cw;
+          const bool have = r.rpos < r.wpos;
+          const bool app = need && have;
+          const uint32_t w = r.ring[(r.rpos & (kRing - 1)) * kThreads];
+          const int sh = app ? 32 - r.nb : 0;
+          r.buf |= app ? ((uint64_t)w << sh) : 0ull;
+          r.nb += app ? 32 : 0;
+          r.rpos += app ? 1u : 0u;
+          const uint32_t e16 = lut[(uint32_t)(r.buf >> (64 - L))];
+          const int l = (int)(e16 >> 12);
+          const uint32_t sym = e16 & 0xFFFu;
+          redo |= (need && !have) || e16 == 0 || l > r.nb || sym >= lim;
+          r.buf <<= l;
+          r.nb -= l;
+          vals[j] = (uint32_t)out_value<MODE>(sym);
+        }
+      }
+      if (redo) {
+        r.buf = buf0;
+        r.nb = nb0;
+        r.rpos = rpos0;
+        r.wpos = wpos0;
+#pragma unroll
+        for (int j = 0; j < kRound; j++) {
+          vals[j] = 0;
+          if (j < cnt) {
+            uint64_t v;
+            if (!decode_symbol(r, lut, glut, L, d, &v)) {
+              atomicOr(err, kErrCorrupt);
+              return;
+            }
+            vals[j] = (uint32_t)out_value<MODE>(v);
           }
-          vals[j] = (uint32_t)out_value<MODE>(v);
         }
       }
       if (vec && cnt == kRound) {
