@@ -439,92 +439,97 @@ __device__ inline uint32_t lane_u32(uint32_t v, uint32_t l) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
 }
 
-__device__ uint32_t small_code(ArrWork& w, uint32_t count, uint32_t* maxd_out) {
+// Lengths of one wave's code with `h` halvings (c -> ceil(c / 2), h times) of
+// lane s's count; returns the longest, sets this lane's length (0 if unused).
+__device__ uint32_t small_lengths(uint32_t count, int h, uint32_t* len_out) {
   const uint32_t lane = (uint32_t)lane_id();
   const uint64_t used = __ballot(count != 0);
   const uint32_t U = (uint32_t)__popcll(used);
-  uint32_t len = 0;  // of this lane's symbol
-  uint32_t md = 0;
   if (U == 1) {
-    len = count ? 1u : 0u;
-    md = 1;
-  } else {
-    for (int h = 0; h < kHalvings; h++) {
-      uint32_t c = count;
-      for (int j = 0; j < h && c > 1; j++) c = (c + 1u) >> 1;
-      // leaves in (count, symbol) order; unused symbols sort last
-      const uint64_t key = lane_sort64(c ? (((uint64_t)c << 13) | lane) : ~0ull);
-      const uint32_t lw = (uint32_t)(key >> 13);   // leaf weight (lane i = leaf i)
-      const uint32_t ls = (uint32_t)(key & 0x1FFFu);
-      uint32_t iw = 0;     // internal node weights (lane k = internal node k)
-      uint32_t lpar = 0;   // parent of leaf i (a node id: internal k is U + k)
-      uint32_t ipar = 0;   // parent of internal node k
-      uint32_t li = 0, ii = 0;
-      constexpr uint32_t kInf = 0xFFFFFFFFu;
-      for (uint32_t nxt = 0; nxt + 1 < U; nxt++) {
-        const uint32_t L0 = li < U ? lane_u32(lw, li) : kInf;
-        const uint32_t L1 = li + 1 < U ? lane_u32(lw, li + 1) : kInf;
-        const uint32_t I0 = ii < nxt ? lane_u32(iw, ii) : kInf;
-        const uint32_t I1 = ii + 1 < nxt ? lane_u32(iw, ii + 1) : kInf;
-        uint32_t node0, node1, w0, w1, lh, ih;
-        if (L0 <= I0) {
-          node0 = li++;
-          w0 = L0;
-          lh = L1;
-          ih = I0;
-        } else {
-          node0 = U + ii++;
-          w0 = I0;
-          lh = L0;
-          ih = I1;
-        }
-        if (lh <= ih) {
-          node1 = li++;
-          w1 = lh;
-        } else {
-          node1 = U + ii++;
-          w1 = ih;
-        }
-        if (lane == nxt) iw = w0 + w1;
-        if (node0 < U) {
-          if (lane == node0) lpar = U + nxt;
-        } else if (lane == node0 - U) {
-          ipar = U + nxt;
-        }
-        if (node1 < U) {
-          if (lane == node1) lpar = U + nxt;
-        } else if (lane == node1 - U) {
-          ipar = U + nxt;
-        }
-      }
-      // depths: the root (internal U - 2) is 0; parents are created after
-      // their children
-      uint32_t idep = 0;
-      for (int k = (int)U - 3; k >= 0; k--) {
-        const uint32_t p = lane_u32(ipar, (uint32_t)k) - U;
-        const uint32_t d = lane_u32(idep, p) + 1;
-        if (lane == (uint32_t)k) idep = d;
-      }
-      // (every lane takes part in the shuffle; only leaves keep the result)
-      const uint32_t pd = (uint32_t)__shfl((int)idep, lane < U ? (int)(lpar - U) : 0, kWave);
-      const uint32_t ldep = lane < U ? pd + 1 : 0;
-      md = ldep;
-#pragma unroll
-      for (int d = kWave / 2; d > 0; d >>= 1) md = max(md, (uint32_t)__shfl_xor((int)md, d, kWave));
-      if (md <= (uint32_t)kMaxLen || h == kHalvings - 1) {
-        // lengths back to symbol lanes: leaf i carries symbol ls
-        const uint64_t k2 = lane_sort64(lane < U ? (((uint64_t)ls << 8) | ldep) : ~0ull);
-        const uint32_t s2 = (uint32_t)(k2 >> 8), d2 = (uint32_t)(k2 & 0xFFu);
-        // lane s now holds the s-th used symbol in ascending order
-        for (uint32_t u = 0; u < U; u++) {
-          const uint32_t su = lane_u32(s2, u), du = lane_u32(d2, u);
-          if (lane == su) len = du;
-        }
-        break;
-      }
+    *len_out = count ? 1u : 0u;
+    return 1;
+  }
+  uint32_t c = count;
+  for (int j = 0; j < h && c > 1; j++) c = (c + 1u) >> 1;
+  // leaves in (count, symbol) order; unused symbols sort last
+  const uint64_t key = lane_sort64(c ? (((uint64_t)c << 13) | lane) : ~0ull);
+  const uint32_t lw = (uint32_t)(key >> 13);   // leaf weight (lane i = leaf i)
+  const uint32_t ls = (uint32_t)(key & 0x1FFFu);
+  uint32_t iw = 0;     // internal node weights (lane k = internal node k)
+  uint32_t lpar = 0;   // parent of leaf i (a node id: internal k is U + k)
+  uint32_t ipar = 0;   // parent of internal node k
+  uint32_t li = 0, ii = 0;
+  constexpr uint32_t kInf = 0xFFFFFFFFu;
+  for (uint32_t nxt = 0; nxt + 1 < U; nxt++) {
+    const uint32_t L0 = li < U ? lane_u32(lw, li) : kInf;
+    const uint32_t L1 = li + 1 < U ? lane_u32(lw, li + 1) : kInf;
+    const uint32_t I0 = ii < nxt ? lane_u32(iw, ii) : kInf;
+    const uint32_t I1 = ii + 1 < nxt ? lane_u32(iw, ii + 1) : kInf;
+    uint32_t node0, node1, w0, w1, lh, ih;
+    if (L0 <= I0) {
+      node0 = li++;
+      w0 = L0;
+      lh = L1;
+      ih = I0;
+    } else {
+      node0 = U + ii++;
+      w0 = I0;
+      lh = L0;
+      ih = I1;
+    }
+    if (lh <= ih) {
+      node1 = li++;
+      w1 = lh;
+    } else {
+      node1 = U + ii++;
+      w1 = ih;
+    }
+    if (lane == nxt) iw = w0 + w1;
+    if (node0 < U) {
+      if (lane == node0) lpar = U + nxt;
+    } else if (lane == node0 - U) {
+      ipar = U + nxt;
+    }
+    if (node1 < U) {
+      if (lane == node1) lpar = U + nxt;
+    } else if (lane == node1 - U) {
+      ipar = U + nxt;
     }
   }
-  // canonical codes: shorter first, ties by symbol
+  // depths: the root (internal U - 2) is 0; parents are created after
+  // their children
+  uint32_t idep = 0;
+  for (int k = (int)U - 3; k >= 0; k--) {
+    const uint32_t p = lane_u32(ipar, (uint32_t)k) - U;
+    const uint32_t d = lane_u32(idep, p) + 1;
+    if (lane == (uint32_t)k) idep = d;
+  }
+  // (every lane takes part in the shuffle; only leaves keep the result)
+  const uint32_t pd = (uint32_t)__shfl((int)idep, lane < U ? (int)(lpar - U) : 0, kWave);
+  const uint32_t ldep = lane < U ? pd + 1 : 0;
+  uint32_t md = ldep;
+#pragma unroll
+  for (int d = kWave / 2; d > 0; d >>= 1) md = max(md, (uint32_t)__shfl_xor((int)md, d, kWave));
+  // lengths back to symbol lanes: leaf i carries symbol ls
+  const uint64_t k2 = lane_sort64(lane < U ? (((uint64_t)ls << 8) | ldep) : ~0ull);
+  const uint32_t s2 = (uint32_t)(k2 >> 8), d2 = (uint32_t)(k2 & 0xFFu);
+  // lane s now holds the s-th used symbol in ascending order
+  uint32_t len = 0;
+  for (uint32_t u = 0; u < U; u++) {
+    const uint32_t su = lane_u32(s2, u), du = lane_u32(d2, u);
+    if (lane == su) len = du;
+  }
+  *len_out = len;
+  return md;
+}
+
+// Canonical codes of one wave's lengths (shorter first, ties by symbol);
+// writes lc, table, U, L and the depth md.
+__device__ void small_codes(ArrWork& w, uint32_t count, uint32_t len, uint32_t md,
+                            uint32_t* maxd_out) {
+  const uint32_t lane = (uint32_t)lane_id();
+  const uint64_t used = __ballot(count != 0);
+  const uint32_t U = (uint32_t)__popcll(used);
   uint32_t first = 0, before = 0;
   {
     uint32_t code = 0;
@@ -551,7 +556,6 @@ __device__ uint32_t small_code(ArrWork& w, uint32_t count, uint32_t* maxd_out) {
     w.L = lmax;
     *maxd_out = md;
   }
-  return len;
 }
 
 // ------------------------------------------------------------------ Huffman size
@@ -673,10 +677,30 @@ __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* p
     return;
   }
   if (nsym <= kWave) {
-    if (wave_id() == 0) {
-      const uint32_t len = small_code(w, cnt[0], maxd);
-      const uint32_t U = (uint32_t)__popcll(__ballot(cnt[0] != 0));
-      finish_wave(w, (unsigned long long)cnt[0] * len, U, n, mx, chunk_log2);
+    // wave h tries h halvings, side by side; the fewest that fit win (the
+    // result of halving one step at a time)
+    __shared__ uint32_t s_cnt[kWave], s_md[kHT / kWave];
+    if (wave_id() == 0) s_cnt[lane_id()] = cnt[0];
+    __syncthreads();
+    const uint32_t c = s_cnt[lane_id()];
+    uint32_t len;
+    const uint32_t md = small_lengths(c, wave_id(), &len);
+    if (lane_id() == 0) s_md[wave_id()] = md;
+    __syncthreads();
+    int pick = -1;
+    for (int h = 0; h < kHT / kWave && pick < 0; h++)
+      if (s_md[h] <= (uint32_t)kMaxLen) pick = h;
+    if (pick < 0 && wave_id() == 0) {  // more halvings than waves: one at a time
+      uint32_t mdh = kMaxLen + 1;
+      for (int h = kHT / kWave; h < kHalvings && mdh > (uint32_t)kMaxLen; h++)
+        mdh = small_lengths(c, h, &len);
+      small_codes(w, c, len, mdh, maxd);
+      finish_wave(w, (unsigned long long)c * len, (uint32_t)__popcll(__ballot(c != 0)), n, mx,
+                  chunk_log2);
+    } else if (wave_id() == pick) {
+      small_codes(w, c, len, md, maxd);
+      finish_wave(w, (unsigned long long)c * len, (uint32_t)__popcll(__ballot(c != 0)), n, mx,
+                  chunk_log2);
     }
     return;
   }
