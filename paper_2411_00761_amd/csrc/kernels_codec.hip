@@ -1381,6 +1381,13 @@ __device__ inline bool store_value(const DecArr& d, uint64_t i, uint64_t v) {
     case 0: reinterpret_cast<uint64_t*>(d.out)[i] = v; break;
     case 1: reinterpret_cast<uint64_t*>(d.out)[i] = (uint64_t)unzigzag64(v); break;
     case 2: reinterpret_cast<uint32_t*>(d.out)[i] = (uint32_t)v; break;
+    case 4: {
+      const int32_t r = (int32_t)unzigzag64(v);
+      const bool small = r >= -127 && r <= 127;
+      reinterpret_cast<int8_t*>(d.out)[i] = small ? (int8_t)r : (int8_t)-128;
+      if (!small) d.esc[i] = r;
+      break;
+    }
     default: reinterpret_cast<uint32_t*>(d.out)[i] = (uint32_t)(int32_t)unzigzag64(v); break;
   }
   return true;
@@ -1476,7 +1483,15 @@ __device__ inline bool decode_symbol(RingReader& r, const uint16_t* lut, const u
 
 template <int MODE>
 __device__ inline uint64_t out_value(uint64_t v) {
-  return (MODE == 1 || MODE == 3) ? (uint64_t)unzigzag64(v) : v;
+  return (MODE == 1 || MODE >= 3) ? (uint64_t)unzigzag64(v) : v;
+}
+
+// Mode 4: a residual as int8, or -128 with the value kept in esc.
+__device__ inline uint32_t byte_of(uint32_t r, const DecArr& d, uint64_t i) {
+  const int32_t v = (int32_t)r;
+  if (v >= -127 && v <= 127) return (uint32_t)(uint8_t)(int8_t)v;
+  ((__attribute__((address_space(1))) int32_t*)d.esc)[i] = v;
+  return 0x80u;
 }
 
 template <int MODE, int K>
@@ -1515,6 +1530,7 @@ __device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const 
   for (int j = 0; j < K; j++) pf[j] = r.pay[min((uint64_t)pfpos + j, last)];
   const uint64_t cbeg = c * C, cend = min(d.n, cbeg + C);
   const bool vec = MODE >= 2 && (reinterpret_cast<uintptr_t>(d.out) & 15) == 0;
+  typedef __attribute__((address_space(1))) uint8_t* GOut8;
   const uint32_t lim = d.limit > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)d.limit;
   for (uint64_t i0 = cbeg; i0 < cend; i0 += kRound) {
     if (pfpos == r.wpos && r.wpos < r.cw && r.wpos + K <= r.rpos + kRing) {
@@ -1584,7 +1600,23 @@ __device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const 
           }
         }
       }
-      if (vec && cnt == kRound) {
+      if (MODE == 4) {
+        // bytes: four values to a word, one 16-byte store per round
+        uint32_t b[kRound];
+#pragma unroll
+        for (int j = 0; j < kRound; j++) b[j] = j < cnt ? byte_of(vals[j], d, i0 + j) : 0u;
+        if (vec && cnt == kRound) {
+          uint32_t wd[kRound / 4];
+#pragma unroll
+          for (int q = 0; q < kRound / 4; q++)
+            wd[q] = b[4 * q] | (b[4 * q + 1] << 8) | (b[4 * q + 2] << 16) | (b[4 * q + 3] << 24);
+          *(GOut128)((GOut8)d.out + i0) = U32x4{wd[0], wd[1], wd[2], wd[3]};
+        } else {
+#pragma unroll
+          for (int j = 0; j < kRound; j++)
+            if (j < cnt) ((GOut8)d.out)[i0 + j] = (uint8_t)b[j];
+        }
+      } else if (vec && cnt == kRound) {
         GOut128 o = (GOut128)((GOut32)d.out + i0);
 #pragma unroll
         for (int q = 0; q < kRound / 4; q++)
@@ -1655,7 +1687,8 @@ __global__ __launch_bounds__(kThreads) void k_decode_huff(const DecArr* arrs,
     case 0: decode_chunk_k<0>(K, d, lut, src, L, c, chunk_log2, ring, err); break;
     case 1: decode_chunk_k<1>(K, d, lut, src, L, c, chunk_log2, ring, err); break;
     case 2: decode_chunk_k<2>(K, d, lut, src, L, c, chunk_log2, ring, err); break;
-    default: decode_chunk_k<3>(K, d, lut, src, L, c, chunk_log2, ring, err); break;
+    case 3: decode_chunk_k<3>(K, d, lut, src, L, c, chunk_log2, ring, err); break;
+    default: decode_chunk_k<4>(K, d, lut, src, L, c, chunk_log2, ring, err); break;
   }
 }
 

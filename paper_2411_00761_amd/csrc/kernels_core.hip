@@ -819,11 +819,25 @@ __global__ __launch_bounds__(kThreads) void k_t_recon_chain(const int32_t* q_ref
         int64_t q[4] = {qr.x, qr.y, qr.z, qr.w};
         for (int j = 0; j < J; j++) {
           float4* o = reinterpret_cast<float4*>(out.p[j][f]) + s4;
-          const int4 r = *reinterpret_cast<const int4*>(o);
-          q[0] += r.x;
-          q[1] += r.y;
-          q[2] += r.z;
-          q[3] += r.w;
+          int32_t rr[4];
+          if (out.r8[j][f]) {
+            const uint32_t b = reinterpret_cast<const uint32_t*>(out.r8[j][f])[s4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+              rr[u] = (int32_t)(int8_t)(uint8_t)(b >> (8 * u));
+              if (rr[u] == -128) rr[u] = reinterpret_cast<const int32_t*>(o)[u];
+            }
+          } else {
+            const int4 r = *reinterpret_cast<const int4*>(o);
+            rr[0] = r.x;
+            rr[1] = r.y;
+            rr[2] = r.z;
+            rr[3] = r.w;
+          }
+          q[0] += rr[0];
+          q[1] += rr[1];
+          q[2] += rr[2];
+          q[3] += rr[3];
           float v[4];
 #pragma unroll
           for (int u = 0; u < 4; u++) {
@@ -845,7 +859,14 @@ __global__ __launch_bounds__(kThreads) void k_t_recon_chain(const int32_t* q_ref
       for (int f = 0; f < F; f++) {
         int64_t q = q_ref[(uint64_t)f * n + s];
         for (int j = 0; j < J; j++) {
-          q += reinterpret_cast<const int32_t*>(out.p[j][f])[s];
+          int32_t r;
+          if (out.r8[j][f]) {
+            r = out.r8[j][f][s];
+            if (r == -128) r = reinterpret_cast<const int32_t*>(out.p[j][f])[s];
+          } else {
+            r = reinterpret_cast<const int32_t*>(out.p[j][f])[s];
+          }
+          q += r;
           if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
             bad = 1;
             q = 0;
@@ -1062,9 +1083,13 @@ void launch_t_recon_chain(const int32_t* q_ref, int F, uint64_t n, const GridDev
                           const ChainOut& out, int J, int32_t* q_last, uint32_t* err,
                           hipStream_t s) {
   int vec = (n % 4 == 0) && al16(q_ref) && (!q_last || al16(q_last));
+  uint64_t per = 0;  // bytes per slot: residuals read and values written
   for (int j = 0; j < J; j++)
-    for (int f = 0; f < F; f++) vec = vec && al16(out.p[j][f]);
-  LCP_TIMED("t_recon", n * (8ull * F * J + 4ull * F + (q_last ? 4ull * F : 0)), s,
+    for (int f = 0; f < F; f++) {
+      vec = vec && al16(out.p[j][f]) && (reinterpret_cast<uintptr_t>(out.r8[j][f]) & 3) == 0;
+      per += out.r8[j][f] ? 5 : 8;
+    }
+  LCP_TIMED("t_recon", n * (per + 4ull * F + (q_last ? 4ull * F : 0)), s,
             k_t_recon_chain<<<grid_for(vec ? n / 4 : n, kThreads * 2, 1u << 16), kThreads, 0, s>>>(
                 q_ref, F, n, g, out, J, q_last, err, vec));
 }

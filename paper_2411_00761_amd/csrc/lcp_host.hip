@@ -18,6 +18,8 @@ namespace {
 
 // Temporal frames coded back to back before the host reads their outcomes.
 constexpr int kTRun = 8;
+// Temporal frames whose residuals one decode launch keeps as bytes.
+constexpr int kDecSlots = kChainMax;
 
 // ------------------------------------------------------------------ grids
 struct HostGrid {
@@ -91,6 +93,7 @@ struct lcp_plan_s {
   uint64_t *keys0, *keys1, *ids, *v_id, *v_cnt, *prel;
   uint32_t *vals0, *vals1, *hist, *flags, *starts, *v_slot, *chunk_words, *lut, *corner;
   uint8_t* v_byte;  // temporal residuals as bytes (multi-frame plans; escapes in v_slot)
+  int8_t* dres8;    // decoded temporal residuals as bytes, kDecSlots frames (multi-frame)
   uint32_t* stage;  // Huffman payload staging, one slot per chunk
   uint64_t* scan_tmp;
   size_t scan_tmp_n;
@@ -1244,40 +1247,21 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
       j0 = j1;
     }
   } else {
-  // ---- entropy decoding of every array that lands in the output buffers
-  int A = 0;
-  uint64_t bytes = 0;
+  // ---- frames in sub-groups with at most kDecSlots temporal frames: one
+  // decode launch for every array of the sub-group that lands in an output
+  // buffer (a temporal frame's residuals go to a byte slot, escapes to its
+  // output buffer), then reconstruction in stream order.  Consecutive
+  // temporal frames each coded against the previous one form a chain
+  // reconstructed in one pass; only the chain's last codes are kept (a later
+  // record can only reference the frame just before it or an anchor, which is
+  // spatial).
   int cl = nf ? H[0].cl : 10;
   bool same_cl = true;
   for (uint64_t j = 0; j < nf; j++) same_cl &= H[j].cl == cl;
-  for (uint64_t j = 0; j < nf && same_cl; j++) {
-    const ParsedHdr& h = H[j];
-    const uint8_t* rec = reinterpret_cast<const uint8_t*>(blobs[j].data);
-    for (int a = (h.mode == 0 ? 2 : 0); a < h.A; a++) {
-      const int f = h.mode == 0 ? a - 2 : a;
-      DecArr& d = P->arrtab_host[A++];
-      d.data = rec + h.aoff[a];
-      d.nbytes = h.anb[a];
-      d.n = h.an[a];
-      d.coder = h.coder[a];
-      d.param = h.param[a];
-      d.used = h.used[a];
-      d.out = outs[j].fields[f];
-      d.mode = h.mode == 0 ? 2 : 3;
-      d.limit = h.mode == 0 ? (f < 3 ? (1ull << h.k) : (uint64_t)kQLimit) : (1ull << 25);
-      bytes += h.anb[a] + 4 * h.an[a];
-    }
-  }
-  if (same_cl) {
-    lcp_status st = decode_arrays(P, 0, A, cl, bytes, s);
-    if (st) return st;
-  }
-  // ---- reconstruction in stream order.  Consecutive temporal frames each coded
-  // against the previous one form a chain reconstructed in one pass; only the
-  // chain's last codes are kept (a later record can only reference the frame
-  // just before it or an anchor, which is spatial).
-  int extra = A;  // staging slots for the id / count arrays of spatial frames
+  const int cap_arrays = kMaxBatchArrays + 2 * kMaxBatchFrames;
+  int next = 0;  // descriptor slots used by this call
   ChainOut chain;
+  memset(&chain, 0, sizeof(chain));
   int chain_len = 0, chain_ref = -1;
   uint64_t chain_last = 0;
   GridDev chain_g;
@@ -1288,93 +1272,129 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
                            P->dqpool[dq[chain_last]], P->err, s);
     chain_len = 0;
   };
-  for (uint64_t j = 0; j < nf; j++) {
+  // the arrays of frame j that land in its output buffers; tslot >= 0 puts a
+  // temporal frame's residuals into that byte slot
+  auto add_arrays = [&](uint64_t j, int tslot, uint64_t* bytes) {
     const ParsedHdr& h = H[j];
-    const uint64_t n = h.n;
     const uint8_t* rec = reinterpret_cast<const uint8_t*>(blobs[j].data);
-    GridDev gd;
-    memset(&gd, 0, sizeof(gd));
-    for (int f = 0; f < F; f++) {
-      gd.m[f] = h.m[f];
-      gd.eb_q[f] = h.eb_q[f];
-    }
-    OutPtrs op;
-    memset(&op, 0, sizeof(op));
-    for (int f = 0; f < F; f++) op.p[f] = outs[j].fields[f];
-    int32_t* q_slot = multi ? P->dqpool[dq[j]] : nullptr;
-    // staging slots: at most kMaxF + 2 per frame beyond the batched arrays
-    if (extra + kMaxF + 2 > kMaxBatchArrays + 2 * kMaxBatchFrames) return LCP_ERR_ARG;
-    if (!same_cl) {  // mixed chunk sizes: decode this frame's arrays on their own
-      int a0 = extra;
-      for (int a = (h.mode == 0 ? 2 : 0); a < h.A; a++) {
-        const int f = h.mode == 0 ? a - 2 : a;
-        DecArr& d = P->arrtab_host[extra++];
-        d.data = rec + h.aoff[a];
-        d.nbytes = h.anb[a];
-        d.n = h.an[a];
-        d.coder = h.coder[a];
-        d.param = h.param[a];
-        d.used = h.used[a];
-        d.out = outs[j].fields[f];
-        d.mode = h.mode == 0 ? 2 : 3;
-        d.limit = h.mode == 0 ? (f < 3 ? (1ull << h.k) : (uint64_t)kQLimit) : (1ull << 25);
+    for (int a = (h.mode == 0 ? 2 : 0); a < h.A; a++) {
+      const int f = h.mode == 0 ? a - 2 : a;
+      DecArr& d = P->arrtab_host[next++];
+      d.data = rec + h.aoff[a];
+      d.nbytes = h.anb[a];
+      d.n = h.an[a];
+      d.coder = h.coder[a];
+      d.param = h.param[a];
+      d.used = h.used[a];
+      d.out = outs[j].fields[f];
+      d.esc = nullptr;
+      d.mode = h.mode == 0 ? 2 : 3;
+      if (h.mode == 1 && tslot >= 0) {
+        d.mode = 4;
+        d.out = P->dres8 + ((uint64_t)tslot * F + f) * P->N;
+        d.esc = reinterpret_cast<int32_t*>(outs[j].fields[f]);
       }
-      lcp_status st = decode_arrays(P, a0, extra - a0, h.cl, 0, s);
+      d.limit = h.mode == 0 ? (f < 3 ? (1ull << h.k) : (uint64_t)kQLimit) : (1ull << 25);
+      if (bytes) *bytes += h.anb[a] + 4 * h.an[a];
+    }
+  };
+  for (uint64_t g0 = 0; g0 < nf;) {
+    uint64_t g1 = g0;
+    for (int nt = 0; g1 < nf && (H[g1].mode == 0 || nt < kDecSlots); g1++) nt += H[g1].mode;
+    std::vector<int> tslot(g1 - g0, -1);
+    if (same_cl) {
+      const int a0 = next;
+      uint64_t bytes = 0;
+      int t = 0;
+      for (uint64_t j = g0; j < g1; j++) {
+        if (next + kMaxArrays > cap_arrays) return LCP_ERR_ARG;
+        if (H[j].mode == 1) tslot[j - g0] = t++;
+        add_arrays(j, tslot[j - g0], &bytes);
+      }
+      lcp_status st = decode_arrays(P, a0, next - a0, cl, bytes, s);
       if (st) return st;
     }
-    if (h.mode == 0) {
-      flush_chain();
-      const uint64_t B = h.B;
-      unsigned __int128 tot = (unsigned __int128)h.bn[0] * h.bn[1] * h.bn[2];
-      if (h.bn[0] == 0 || h.bn[1] == 0 || h.bn[2] == 0 || tot >= ((unsigned __int128)1 << 63))
-        return LCP_ERR_CORRUPT;
-      const uint64_t total_blocks = (uint64_t)tot;
-      for (int a = 0; a < 2; a++) {
-        DecArr& d = P->arrtab_host[extra + a];
-        d.data = rec + h.aoff[a];
-        d.nbytes = h.anb[a];
-        d.n = h.an[a];
-        d.coder = h.coder[a];
-        d.param = h.param[a];
-        d.used = h.used[a];
-        d.out = a == 0 ? (void*)P->v_id : (void*)P->v_cnt;
-        d.mode = a;  // ids raw, counts unzigzagged
-        d.limit = a == 0 ? total_blocks : ~0ull;
+    for (uint64_t j = g0; j < g1; j++) {
+      const ParsedHdr& h = H[j];
+      const uint64_t n = h.n;
+      const uint8_t* rec = reinterpret_cast<const uint8_t*>(blobs[j].data);
+      GridDev gd;
+      memset(&gd, 0, sizeof(gd));
+      for (int f = 0; f < F; f++) {
+        gd.m[f] = h.m[f];
+        gd.eb_q[f] = h.eb_q[f];
       }
-      lcp_status st = decode_arrays(P, extra, 2, h.cl, 0, s);
-      if (st) return st;
-      extra += 2;
-      uint64_t* ids = P->v_id;
-      uint64_t* cnt = P->v_cnt;
-      uint64_t* cum = P->ids;
-      scan_device<uint64_t>(ids, B, nullptr, false, P->scan_tmp, s);
-      scan_device<uint64_t>(cnt, B, nullptr, false, P->scan_tmp, s);
-      HIP_OK(hipMemcpyAsync(cum, cnt, B * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
-      scan_device<uint64_t>(cum, B, nullptr, false, P->scan_tmp, s);
-      launch_fill_u32(P->flags, n, 0u, s);
-      launch_s_blocks(ids, cnt, cum, B, n, total_blocks, h.bn, h.k, P->corner, P->flags,
-                      P->err, s);
-      uint32_t* tmp32 = reinterpret_cast<uint32_t*>(P->scan_tmp);
-      scan_device<uint32_t>(P->flags, n, nullptr, false, tmp32, s);
-      for (int d = 0; d < 3; d++)
-        scan_device<uint32_t>(reinterpret_cast<uint32_t*>(outs[j].fields[d]), n, nullptr, false,
-                              tmp32, s);
-      launch_s_recon(P->flags, P->corner, B, F, n, h.k, gd, op, q_slot, P->err, s);
-    } else {
-      const bool extend = chain_len > 0 && chain_len < kChainMax && j > 0 &&
-                          chain_last == j - 1 && refq[j] == dq[j - 1] && H[j - 1].n == n &&
-                          memcmp(&chain_g, &gd, sizeof(gd)) == 0;
-      if (!extend) {
+      OutPtrs op;
+      memset(&op, 0, sizeof(op));
+      for (int f = 0; f < F; f++) op.p[f] = outs[j].fields[f];
+      int32_t* q_slot = multi ? P->dqpool[dq[j]] : nullptr;
+      if (next + kMaxArrays + 2 > cap_arrays) return LCP_ERR_ARG;
+      if (!same_cl) {  // mixed chunk sizes: decode this frame's arrays on their own
+        const int a0 = next;
+        add_arrays(j, -1, nullptr);
+        lcp_status st = decode_arrays(P, a0, next - a0, h.cl, 0, s);
+        if (st) return st;
+      }
+      if (h.mode == 0) {
         flush_chain();
-        chain_ref = refq[j];
-        chain_g = gd;
+        const uint64_t B = h.B;
+        unsigned __int128 tot = (unsigned __int128)h.bn[0] * h.bn[1] * h.bn[2];
+        if (h.bn[0] == 0 || h.bn[1] == 0 || h.bn[2] == 0 || tot >= ((unsigned __int128)1 << 63))
+          return LCP_ERR_CORRUPT;
+        const uint64_t total_blocks = (uint64_t)tot;
+        for (int a = 0; a < 2; a++) {
+          DecArr& d = P->arrtab_host[next + a];
+          d.data = rec + h.aoff[a];
+          d.nbytes = h.anb[a];
+          d.n = h.an[a];
+          d.coder = h.coder[a];
+          d.param = h.param[a];
+          d.used = h.used[a];
+          d.out = a == 0 ? (void*)P->v_id : (void*)P->v_cnt;
+          d.esc = nullptr;
+          d.mode = a;  // ids raw, counts unzigzagged
+          d.limit = a == 0 ? total_blocks : ~0ull;
+        }
+        lcp_status st = decode_arrays(P, next, 2, h.cl, 0, s);
+        if (st) return st;
+        next += 2;
+        uint64_t* ids = P->v_id;
+        uint64_t* cnt = P->v_cnt;
+        uint64_t* cum = P->ids;
+        scan_device<uint64_t>(ids, B, nullptr, false, P->scan_tmp, s);
+        scan_device<uint64_t>(cnt, B, nullptr, false, P->scan_tmp, s);
+        HIP_OK(hipMemcpyAsync(cum, cnt, B * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+        scan_device<uint64_t>(cum, B, nullptr, false, P->scan_tmp, s);
+        launch_fill_u32(P->flags, n, 0u, s);
+        launch_s_blocks(ids, cnt, cum, B, n, total_blocks, h.bn, h.k, P->corner, P->flags,
+                        P->err, s);
+        uint32_t* tmp32 = reinterpret_cast<uint32_t*>(P->scan_tmp);
+        scan_device<uint32_t>(P->flags, n, nullptr, false, tmp32, s);
+        for (int d = 0; d < 3; d++)
+          scan_device<uint32_t>(reinterpret_cast<uint32_t*>(outs[j].fields[d]), n, nullptr, false,
+                                tmp32, s);
+        launch_s_recon(P->flags, P->corner, B, F, n, h.k, gd, op, q_slot, P->err, s);
+      } else {
+        const bool extend = chain_len > 0 && chain_len < kChainMax && j > g0 &&
+                            chain_last == j - 1 && refq[j] == dq[j - 1] && H[j - 1].n == n &&
+                            memcmp(&chain_g, &gd, sizeof(gd)) == 0;
+        if (!extend) {
+          flush_chain();
+          chain_ref = refq[j];
+          chain_g = gd;
+        }
+        const int t = tslot[j - g0];
+        for (int f = 0; f < F; f++) {
+          chain.p[chain_len][f] = outs[j].fields[f];
+          chain.r8[chain_len][f] = t >= 0 ? P->dres8 + ((uint64_t)t * F + f) * P->N : nullptr;
+        }
+        chain_len++;
+        chain_last = j;
       }
-      for (int f = 0; f < F; f++) chain.p[chain_len][f] = outs[j].fields[f];
-      chain_len++;
-      chain_last = j;
     }
+    flush_chain();
+    g0 = g1;
   }
-  flush_chain();
   }
   {
     lcp_status st = read_ret(P, 1, s);
@@ -1450,8 +1470,13 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   D.add(&P->flags, NB);
   D.add(&P->starts, NB);
   D.add(&P->v_slot, (uint64_t)F * NB);
-  if (P->p.multi_frame) D.add(&P->v_byte, (uint64_t)F * NB);
-  else P->v_byte = nullptr;
+  if (P->p.multi_frame) {
+    D.add(&P->v_byte, (uint64_t)F * NB);
+    D.add(&P->dres8, (uint64_t)kDecSlots * F * NB);
+  } else {
+    P->v_byte = nullptr;
+    P->dres8 = nullptr;
+  }
   D.add(&P->chunk_words, P->cw_cap);
   D.add(&P->stage, P->stage_cap);
   D.add(&P->lut, (uint64_t)(kMaxBatchArrays + 2 * kMaxBatchFrames) << kMaxLen);

@@ -118,8 +118,10 @@ struct DecArr {
   int coder, param;
   uint32_t used;
   void* out;
-  int mode;        // 0 u64, 1 unzigzag -> int64 in u64, 2 u32, 3 unzigzag -> int32 in u32
+  int mode;        // 0 u64, 1 unzigzag -> int64 in u64, 2 u32, 3 unzigzag -> int32 in u32,
+                   // 4 unzigzag -> int8 in out, -128 marking a value kept in esc (int32)
   uint64_t limit;  // raw values >= limit are corrupt
+  int32_t* esc;    // mode 4: where values outside [-127, 127] go (same index)
 };
 
 // Device error word bits.
@@ -244,6 +246,9 @@ void launch_install(const void* src, void* dst, size_t bytes, hipStream_t s);
 constexpr int kChainMax = 16;
 struct ChainOut {
   float* p[kChainMax][kMaxF];
+  // non-null: the frame's residuals as int8 (-128: the int32 residual is in p
+  // at the same index); null: the int32 residuals are in p itself
+  const int8_t* r8[kChainMax][kMaxF];
 };
 void launch_t_recon_chain(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,
                           const ChainOut& out, int J, int32_t* q_last, uint32_t* err,
