@@ -175,10 +175,12 @@ lcp_status lcp_select(lcp_plan_t plan, int* decision);
 
 const char* lcp_status_string(lcp_status status);
 
-/* Kernel timing for roofline measurement: while a name is set, every launch of
- * the kernel with that name is bracketed by HIP events on its stream; the
- * accumulated time (ms), launch count and algorithmic bytes are read back with
- * lcp_kernel_timer_read.  Pass NULL to stop. */
+/* Kernel timing for roofline measurement: while a name is set, one launch in
+ * eight of the kernel with that name (the first, the ninth, ...) carries HIP
+ * events on its own dispatch; the accumulated time (ms), count and algorithmic
+ * bytes of the timed launches are read back with lcp_kernel_timer_read.
+ * Sampling keeps the events' cost on the stream (a few microseconds around each
+ * timed launch) out of the other launches.  Pass NULL to stop. */
 lcp_status lcp_kernel_timer_set(lcp_plan_t plan, const char* kernel_name);
 lcp_status lcp_kernel_timer_read(lcp_plan_t plan, double* total_ms, uint64_t* launches,
                                  uint64_t* bytes);

@@ -1758,9 +1758,8 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
   const uint32_t* pre_fixed = L.pre + 2 * (NA + 1);
   const uint32_t* pre_copy = L.pre + 3 * (NA + 1);
   if (!hist_done)
-    LCP_TIMED("hist", L.values * 4ull, s,
-              k_hist<<<L.hist_blocks, kThreads, 0, s>>>(L.arrs, pre_hist, NA, X.hist_part,
-                                                        X.hist_max));
+    launch_timed("hist", L.values * 4ull, k_hist, L.hist_blocks, kThreads, 0, s,
+               L.arrs, pre_hist, NA, X.hist_part, X.hist_max);
   // the plain build (and its codes) per array; the halving candidates and their
   // codes only run for arrays whose plain build is too deep.  Temporal residual
   // arrays (hist_done) halve inline: their alphabets are short and the fallback
@@ -1775,21 +1774,20 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
   {
     const size_t shm = (size_t)slot64 * 4;
     const uint32_t g = L.chunk_blocks;
-    LCP_TIMED("pack_huff", L.values * 6ull, s, {
-      switch (chunk_log2) {
-        case 9: k_pack_huff<2><<<g, kThreads, shm, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, slot64, err); break;
-        case 10: k_pack_huff<4><<<g, kThreads, shm, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, slot64, err); break;
-        case 11: k_pack_huff<8><<<g, kThreads, shm, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, slot64, err); break;
-        case 12: k_pack_huff<16><<<g, kThreads, shm, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, slot64, err); break;
-        default: k_pack_huff<1><<<g, kThreads, shm, s>>>(L.arrs, work, pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, slot64, err); break;
-      }
-    });
+    auto* kernel = k_pack_huff<1>;
+    switch (chunk_log2) {
+      case 9: kernel = k_pack_huff<2>; break;
+      case 10: kernel = k_pack_huff<4>; break;
+      case 11: kernel = k_pack_huff<8>; break;
+      case 12: kernel = k_pack_huff<16>; break;
+      default: break;
+    }
+    launch_timed("pack_huff", L.values * 6ull, kernel, g, kThreads, shm, s, L.arrs, work,
+                 pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, slot64, err);
   }
   k_layout<<<1, kHT, 0, s>>>(work, L.recs, L.rec0, L.R, out, cap, offs, base, err);
-  LCP_TIMED("emit", L.values * 6ull, s,
-            k_emit<<<L.fixed_blocks + L.copy_blocks, kThreads, 0, s>>>(
-                L.arrs, work, L.recs, pre_fixed, L.fixed_blocks, pre_copy, NA, X.chunk_words,
-                X.stage, slot32, slot64, out, err));
+  launch_timed("emit", L.values * 6ull, k_emit, L.fixed_blocks + L.copy_blocks, kThreads, 0, s,
+               L.arrs, work, L.recs, pre_fixed, L.fixed_blocks, pre_copy, NA, X.chunk_words, X.stage, slot32, slot64, out, err);
 }
 
 uint32_t decode_blocks(const DecArr& d, int chunk_log2, bool huff) {
@@ -1812,12 +1810,11 @@ void launch_decode(const DecArr* arrs_dev, int A, const uint32_t* huff_prefix_de
   if (lut_log2 > kMaxLen) lut_log2 = kMaxLen;
   const size_t shm = (size_t)kThreads * kRing * 4 + (((size_t)2 << lut_log2) + 3) / 4 * 4;
   if (huff_blocks)
-    LCP_TIMED("decode_huff", bytes, s,
-              k_decode_huff<<<huff_blocks, kThreads, shm, s>>>(arrs_dev, huff_prefix_dev, A,
-                                                              chunk_log2, lut, lut_log2, err));
+    launch_timed("decode_huff", bytes, k_decode_huff, huff_blocks, kThreads, shm, s,
+               arrs_dev, huff_prefix_dev, A, chunk_log2, lut, lut_log2, err);
   if (fixed_blocks)
-    LCP_TIMED("decode_fixed", bytes, s,
-              k_decode_fixed<<<fixed_blocks, kThreads, 0, s>>>(arrs_dev, fixed_prefix_dev, A, err));
+    launch_timed("decode_fixed", bytes, k_decode_fixed, fixed_blocks, kThreads, 0, s,
+               arrs_dev, fixed_prefix_dev, A, err);
 }
 
 }  // namespace lcp

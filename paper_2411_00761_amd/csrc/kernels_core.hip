@@ -916,16 +916,16 @@ uint32_t seg_ext_blocks(uint64_t n) { return grid_for(n / 4 + 1, kThreads * 4, k
 
 void launch_extent_b(const SegDev* S, const uint32_t* pre_ext, uint32_t ext_blocks, int R, int F,
                      uint32_t* ext, uint32_t* part, uint32_t* err, uint64_t bytes, hipStream_t s) {
-  LCP_TIMED("extent", bytes, s,
-            k_extent_b<<<dim3(ext_blocks, F), kThreads, 0, s>>>(S, pre_ext, R, part, err));
+  launch_timed("extent", bytes, k_extent_b, dim3(ext_blocks, F), kThreads, 0, s,
+               S, pre_ext, R, part, err);
   k_extent_final_b<<<dim3(R, F), kThreads, 0, s>>>(part, pre_ext, R, F, ext_blocks, ext);
 }
 
 void launch_quant_key_b(const SegDev* S, const uint32_t* pre_1k, uint32_t blocks, int R,
                         uint64_t* keys, uint32_t* vals, uint64_t* prel, uint64_t ntot,
                         hipStream_t s) {
-  LCP_TIMED("quant_key", ntot * (12 + 20), s,
-            k_quant_key_b<<<blocks, kThreads, 0, s>>>(S, pre_1k, R, keys, vals, prel));
+  launch_timed("quant_key", ntot * (12 + 20), k_quant_key_b, blocks, kThreads, 0, s,
+               S, pre_1k, R, keys, vals, prel);
 }
 
 void launch_runs_b(const uint64_t* keys, const SegDev* S, const uint32_t* pre_1k, uint32_t blocks,
@@ -947,9 +947,8 @@ void launch_slot_syms_b(const SegDev* S, const uint32_t* pre_256, uint32_t block
                         const uint32_t* perm, const uint64_t* prel, uint64_t ntot, uint32_t* v_rel,
                         uint32_t* v_sup, int32_t* q_slot, hipStream_t s) {
   uint64_t bytes = ntot * (4 + 8 + 4ull * (F - 3) + 4ull * F + (q_slot ? 16ull * F : 0));
-  LCP_TIMED("slot_syms", bytes, s,
-            k_slot_syms_b<<<blocks, kThreads, 0, s>>>(S, pre_256, R, F, perm, prel, ntot, v_rel,
-                                                     v_sup, q_slot));
+  launch_timed("slot_syms", bytes, k_slot_syms_b, blocks, kThreads, 0, s,
+               S, pre_256, R, F, perm, prel, ntot, v_rel, v_sup, q_slot);
 }
 
 void launch_copy_perm_b(const uint32_t* perm, const SegDev* S, const uint32_t* pre_1k,
@@ -969,9 +968,8 @@ int radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, const Seg
     uint32_t* vout = cur ? v0 : v1;
     k_radix_hist<<<ntiles, kThreads, 0, s>>>(kin, S, pre_tile, R, shift, hist);
     scan_device<uint32_t>(hist, entries, nullptr, true, tmp32, s);
-    LCP_TIMED("radix_scatter", ntot * 24, s,
-              k_radix_scatter<<<ntiles, kThreads, 0, s>>>(kin, vin, kout, vout, S, pre_tile, R,
-                                                          shift, hist, entries, ntot));
+    launch_timed("radix_scatter", ntot * 24, k_radix_scatter, ntiles, kThreads, 0, s,
+               kin, vin, kout, vout, S, pre_tile, R, shift, hist, entries, ntot);
     cur ^= 1;
   }
   return cur;
@@ -1028,9 +1026,8 @@ void launch_s_blocks_b(const uint64_t* ids, const uint64_t* cnt, const uint64_t*
 void launch_s_recon_b(const uint32_t* blk, const uint32_t* corner, const uint32_t* v,
                       const DSegDev* D, const uint32_t* pre_slot, uint32_t blocks, int R, int F,
                       uint64_t Btot, uint64_t ntot, uint32_t* err, hipStream_t s) {
-  LCP_TIMED("s_recon", ntot * (4 + 12 + 8ull * F), s,
-            k_s_recon_b<<<blocks, kThreads, 0, s>>>(blk, corner, v, D, pre_slot, R, F, Btot, ntot,
-                                                    err));
+  launch_timed("s_recon", ntot * (4 + 12 + 8ull * F), k_s_recon_b, blocks, kThreads, 0, s,
+               blk, corner, v, D, pre_slot, R, F, Btot, ntot, err);
 }
 
 inline bool al16(const void* p) { return ((uintptr_t)p & 15) == 0; }
@@ -1043,10 +1040,8 @@ void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
                   (!v8 || al16(v8));
   // algorithmic bytes: permutation, x and reference codes read; residuals
   // (bytes, or u32) and new codes written
-  LCP_TIMED("t_resid", n * (4 + 12ull * F + (v8 ? 1ull : 4ull) * F), s,
-            k_t_resid<<<grid_for(vec ? n / 4 : n, kThreads * 2, 2048), kThreads,
-                        (size_t)F * (kThreads / kWave) * kResPriv * 4, s>>>(
-                x, F, n, g, perm_ref, q_ref, v8, v_res, q_new, err, vec, hist_part, hist_max));
+  launch_timed("t_resid", n * (4 + 12ull * F + (v8 ? 1ull : 4ull) * F), k_t_resid, grid_for(vec ? n / 4 : n, kThreads * 2, 2048), kThreads, (size_t)F * (kThreads / kWave) * kResPriv * 4, s,
+               x, F, n, g, perm_ref, q_ref, v8, v_res, q_new, err, vec, hist_part, hist_max);
 }
 
 void launch_t_codes(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
@@ -1065,18 +1060,16 @@ void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, ui
 void launch_s_recon(const uint32_t* blk, const uint32_t* corner, uint64_t B, int F, uint64_t n,
                     int k, const GridDev& g, const OutPtrs& out, int32_t* q_slot, uint32_t* err,
                     hipStream_t s) {
-  LCP_TIMED("s_recon", n * (4 + 12 + 8ull * F + (q_slot ? 4ull * F : 0)), s,
-            k_s_recon<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(
-                blk, corner, B, F, n, k, g, out, q_slot, err));
+  launch_timed("s_recon", n * (4 + 12 + 8ull * F + (q_slot ? 4ull * F : 0)), k_s_recon, grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s,
+               blk, corner, B, F, n, k, g, out, q_slot, err);
 }
 
 void launch_t_recon(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,
                     const OutPtrs& out, int32_t* q_slot, uint32_t* err, hipStream_t s) {
   int vec = (n % 4 == 0) && al16(q_ref) && (!q_slot || al16(q_slot));
   for (int f = 0; f < F; f++) vec = vec && al16(out.p[f]);
-  LCP_TIMED("t_recon", n * (12ull * F + (q_slot ? 4ull * F : 0)), s,
-            k_t_recon<<<grid_for(vec ? n / 4 : n, kThreads * 2, 1u << 16), kThreads, 0, s>>>(
-                q_ref, F, n, g, out, q_slot, err, vec));
+  launch_timed("t_recon", n * (12ull * F + (q_slot ? 4ull * F : 0)), k_t_recon, grid_for(vec ? n / 4 : n, kThreads * 2, 1u << 16), kThreads, 0, s,
+               q_ref, F, n, g, out, q_slot, err, vec);
 }
 
 void launch_t_recon_chain(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,
@@ -1089,9 +1082,8 @@ void launch_t_recon_chain(const int32_t* q_ref, int F, uint64_t n, const GridDev
       vec = vec && al16(out.p[j][f]) && (reinterpret_cast<uintptr_t>(out.r8[j][f]) & 3) == 0;
       per += out.r8[j][f] ? 5 : 8;
     }
-  LCP_TIMED("t_recon", n * (per + 4ull * F + (q_last ? 4ull * F : 0)), s,
-            k_t_recon_chain<<<grid_for(vec ? n / 4 : n, kThreads * 2, 1u << 16), kThreads, 0, s>>>(
-                q_ref, F, n, g, out, J, q_last, err, vec));
+  launch_timed("t_recon", n * (per + 4ull * F + (q_last ? 4ull * F : 0)), k_t_recon_chain, grid_for(vec ? n / 4 : n, kThreads * 2, 1u << 16), kThreads, 0, s,
+               q_ref, F, n, g, out, J, q_last, err, vec);
 }
 
 void launch_gather_headers(const uint64_t* tab, int nrec, int stage, uint8_t* dst, hipStream_t s) {

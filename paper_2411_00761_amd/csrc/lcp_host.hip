@@ -16,8 +16,17 @@ using namespace lcp;
 
 namespace {
 
-// Temporal frames coded back to back before the host reads their outcomes.
-constexpr int kTRun = 8;
+// Temporal frames coded back to back before the host reads their outcomes: a
+// run starts at kTRunStart frames and doubles after each run that commits in
+// full, up to kTRun; a run broken part-way starts over at kTRunStart, so the
+// work a misprediction throws away stays small while long T stretches pay one
+// host round trip per kTRun frames.
+constexpr int kTRun = 32;
+constexpr int kTRunStart = 8;
+// The kernel timer brackets one launch in kTimerStride of the named kernel:
+// each timed launch costs the stream some microseconds on either side (the
+// events' own packets), which a sampled average keeps out of the rest.
+constexpr uint64_t kTimerStride = 8;
 // Temporal frames whose residuals one decode launch keeps as bytes.
 constexpr int kDecSlots = kChainMax;
 
@@ -103,6 +112,7 @@ struct lcp_plan_s {
   unsigned long long *ret_dev, *ret_host;
   uint32_t* err;  // the error word (low half of ret_dev[0])
   bool err_clean = false;  // the error word is known to be zero at the stream's tail
+  int run_len = kTRunStart;  // frames the next temporal run may take
   // temporal runs (frames coded back to back, one read-back per run): per
   // frame [4k] error word, [4k + 1, 4k + 3) record start and end
   unsigned long long *run_dev, *run_host;
@@ -160,6 +170,7 @@ struct lcp_plan_s {
   std::vector<uint64_t> ev_bytes;
   double timer_ms = 0;
   uint64_t timer_launches = 0, timer_bytes = 0;
+  uint64_t timer_seen = 0;  // launches of the named kernel since the name was set
 };
 
 namespace {
@@ -878,7 +889,7 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
 // While LCP-FSM stays in its T state every frame is coded with LCP-T against
 // the frame before it (Alg. 1: the batch anchor for the first frame of a
 // batch), and the host only needs a frame's outcome to learn that it still
-// holds.  A run therefore enqueues up to kTRun such frames back to back, each
+// holds.  A run therefore enqueues several such frames back to back, each
 // with its own error word and offsets, each record placed on the device right
 // behind the previous one, and reads the outcomes back once.  Frames are then
 // taken in order; the first whose outcome differs from the prediction (an
@@ -906,7 +917,7 @@ int plan_run(const lcp_plan_s* P, const lcp_frame_in* fr, uint64_t nf, uint64_t 
   RefState prev = P->prev;
   uint64_t seq = P->seq, used = 0;
   int D = 0;
-  for (; D < kTRun && (uint64_t)D < nf; D++) {
+  for (; D < P->run_len && (uint64_t)D < nf; D++) {
     const lcp_frame_in& f = fr[D];
     if (f.n == 0 || f.n > P->N || f.method < 0 || f.method > 2) break;
     bool ok = true;
@@ -962,6 +973,7 @@ lcp_status run_t(lcp_plan_s* P, const lcp_frame_in* fr, int D, const RunFrame* r
     ends[c] = end;
   }
   *committed = c;
+  P->run_len = c < D ? kTRunStart : (D == P->run_len && D < kTRun ? 2 * D : P->run_len);
   // the last committed frame's codes were overwritten if the frame two after
   // it was launched
   if (c >= 1 && c + 1 < D) {
@@ -1712,20 +1724,15 @@ lcp_status plan_setup(const lcp_params* params, const float* const* sample_field
 }  // namespace
 
 namespace lcp {
-bool ktimer_on(const char* name) {
-  return g_timer_plan && g_timer_plan->timer_name[0] && strcmp(g_timer_plan->timer_name, name) == 0;
-}
-void ktimer_begin(hipStream_t s) {
+bool ktimer_events(const char* name, uint64_t bytes, hipEvent_t* start, hipEvent_t* stop) {
   lcp_plan_s* P = g_timer_plan;
-  hipEvent_t a = timer_event(P), b = timer_event(P);
-  (void)hipEventRecord(a, s);
-  P->ev_pending.push_back({a, b});
-  P->ev_bytes.push_back(0);
-}
-void ktimer_end(hipStream_t s, uint64_t bytes) {
-  lcp_plan_s* P = g_timer_plan;
-  (void)hipEventRecord(P->ev_pending.back().second, s);
-  P->ev_bytes.back() = bytes;
+  if (!P || !P->timer_name[0] || strcmp(P->timer_name, name) != 0) return false;
+  if (P->timer_seen++ % kTimerStride != 0) return false;
+  *start = timer_event(P);
+  *stop = timer_event(P);
+  P->ev_pending.push_back({*start, *stop});
+  P->ev_bytes.push_back(bytes);
+  return true;
 }
 
 lcp_status plan_create_unbound(const lcp_params* params, const float* const* sample_fields,
@@ -1965,6 +1972,7 @@ lcp_status lcp_kernel_timer_set(lcp_plan_t plan, const char* kernel_name) {
   }
   plan->timer_ms = 0;
   plan->timer_launches = 0;
+  plan->timer_seen = 0;
   plan->timer_bytes = 0;
   return LCP_OK;
 }

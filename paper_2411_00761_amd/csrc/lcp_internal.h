@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <stdint.h>
 
 #include "../../include/lcp.h"
@@ -133,18 +134,20 @@ enum : uint32_t {
 };
 
 // ---- kernel timer (lcp_host.hip) ----
-// When the named kernel is being timed, its launches are bracketed by HIP events
-// on their stream; `bytes` is the launch's algorithmic traffic.
-bool ktimer_on(const char* name);
-void ktimer_begin(hipStream_t s);
-void ktimer_end(hipStream_t s, uint64_t bytes);
-#define LCP_TIMED(name, bytes, stream, ...)        \
-  do {                                             \
-    bool timed_ = ::lcp::ktimer_on(name);          \
-    if (timed_) ::lcp::ktimer_begin(stream);       \
-    __VA_ARGS__;                                   \
-    if (timed_) ::lcp::ktimer_end(stream, (bytes)); \
-  } while (0)
+// When the named kernel is being timed, ktimer_events hands out the pair of HIP
+// events for one launch and records `bytes`, the launch's algorithmic traffic.
+// The events ride on the kernel's own dispatch (hipExtLaunchKernel), so they
+// time the kernel alone and add no marker packets between kernels.
+bool ktimer_events(const char* name, uint64_t bytes, hipEvent_t* start, hipEvent_t* stop);
+template <typename K, typename... A>
+inline void launch_timed(const char* name, uint64_t bytes, K kernel, dim3 grid, dim3 block,
+                         uint32_t shm, hipStream_t s, A... args) {
+  hipEvent_t a, b;
+  if (ktimer_events(name, bytes, &a, &b))
+    hipExtLaunchKernelGGL(kernel, grid, block, shm, s, a, b, 0, args...);
+  else
+    kernel<<<grid, block, shm, s>>>(args...);
+}
 
 // ---- lcp_host.hip: plans whose scratch is bound per call (the server) ----
 // A plan with its stream state but no scratch; the block-size search, if asked
