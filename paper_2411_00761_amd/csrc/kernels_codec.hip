@@ -588,8 +588,8 @@ __device__ void finish_block(ArrWork& w, unsigned long long part, uint32_t U, ui
     w.huff_bits = bits;
     w.cand = huff_candidate(U, n, maxv, bits, chunk_log2);
     w.nchunks = (uint32_t)((n + (1ull << chunk_log2) - 1) >> chunk_log2);
-    w.huff_words = 0;
   }
+  if (threadIdx.x < kWordParts) w.huff_words[threadIdx.x] = 0;
 }
 
 // One wave (the small-alphabet path): `part` is this lane's share.
@@ -601,8 +601,8 @@ __device__ void finish_wave(ArrWork& w, unsigned long long part, uint32_t U, uin
     w.huff_bits = part;
     w.cand = huff_candidate(U, n, maxv, part, chunk_log2);
     w.nchunks = (uint32_t)((n + (1ull << chunk_log2) - 1) >> chunk_log2);
-    w.huff_words = 0;
   }
+  if (lane_id() < kWordParts) w.huff_words[lane_id()] = 0;
 }
 
 // One array per workgroup: sums its spread histogram copies (only the bins up
@@ -913,7 +913,9 @@ __device__ void layout_records(ArrWork* W, EncRec* recs, const EncRec& rec0, int
       n = w.n;
       const uint64_t mv = w.maxv;
       const uint32_t L = w.L, cand = w.cand, nc = w.nchunks;
-      const uint64_t hw = w.huff_words;
+      uint64_t hw = 0;
+#pragma unroll
+      for (int q = 0; q < kWordParts; q++) hw += w.huff_words[q];
       U = w.U;
       const int wd = bitwidth64(mv);
       const uint64_t fixed = 4 * ((n * (uint64_t)wd + 31) / 32);
@@ -1165,7 +1167,7 @@ __global__ __launch_bounds__(kThreads) void k_pack_huff(const EncArr* E, ArrWork
   else
     pack_chunks<RUN, uint32_t>(e.in.v, nullptr, n, chunk_log2, lb, nb, lc, buf, sm, cnta, pay,
                                slot32, &words, err);
-  if (threadIdx.x == 0 && words) atomicAdd(&w.huff_words, words);
+  if (threadIdx.x == 0 && words) atomicAdd(&w.huff_words[blockIdx.x % kWordParts], words);
 }
 
 __global__ __launch_bounds__(kHT) void k_layout(ArrWork* W, EncRec* recs, const EncRec rec0,
@@ -1764,8 +1766,8 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
   // codes only run for arrays whose plain build is too deep.  Temporal residual
   // arrays (hist_done) halve inline: their alphabets are short and the fallback
   // launches would cost more than they save.
-  k_huff_build<<<NA, kHT, 0, s>>>(L.arrs, X.hist_part, X.hist_max, work, X.huff_lens, X.huff_maxd,
-                                  hist_done ? 1 : 0, chunk_log2);
+  launch_timed("huff_build", 0, k_huff_build, NA, kHT, 0, s, L.arrs, X.hist_part, X.hist_max,
+               work, X.huff_lens, X.huff_maxd, hist_done ? 1 : 0, chunk_log2);
   if (!hist_done) {
     k_huff_lengths<<<dim3(NA, kHalvings - 1), kHT, 0, s>>>(work, X.huff_lens, X.huff_maxd);
     k_huff_codes<<<NA, kHT, 0, s>>>(L.arrs, work, X.huff_lens, X.huff_maxd, chunk_log2);
@@ -1785,7 +1787,8 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
     launch_timed("pack_huff", L.values * 6ull, kernel, g, kThreads, shm, s, L.arrs, work,
                  pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, slot64, err);
   }
-  k_layout<<<1, kHT, 0, s>>>(work, L.recs, L.rec0, L.R, out, cap, offs, base, err);
+  launch_timed("layout", 0, k_layout, 1, kHT, 0, s, work, L.recs, L.rec0, L.R, out, cap, offs,
+               base, err);
   launch_timed("emit", L.values * 6ull, k_emit, L.fixed_blocks + L.copy_blocks, kThreads, 0, s,
                L.arrs, work, L.recs, pre_fixed, L.fixed_blocks, pre_copy, NA, X.chunk_words, X.stage, slot32, slot64, out, err);
 }

@@ -38,6 +38,7 @@ struct ArrIn {
   // (temporal residuals, which are nearly all small)
   const uint32_t* esc;
 };
+constexpr int kWordParts = 16;
 // Per-array coder workspace in device memory.
 struct ArrWork {
   uint32_t hist[kAlphabet];
@@ -45,7 +46,12 @@ struct ArrWork {
   uint32_t table[kAlphabet];  // used symbols in ascending order: symbol | length << 16
   unsigned long long maxv;
   uint32_t n, U, L, coder, w, nchunks;
-  unsigned long long huff_words, nbytes, off;
+  unsigned long long nbytes, off;
+  // packed Huffman payload words, summed by the packing workgroups into
+  // kWordParts spread totals (workgroup b adds to part b % kWordParts): a
+  // device-scope atomic on one address is serialised across the chip, so a
+  // single total would cost every packing workgroup one turn in that queue
+  unsigned long long huff_words[kWordParts];
   unsigned long long huff_bits;  // code + raw bits of all symbols (no chunk padding)
   uint32_t cand, pad;            // Huffman may be the shorter coding: pack it
 };
