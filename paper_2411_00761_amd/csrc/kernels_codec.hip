@@ -17,6 +17,7 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr int kHT = 1024;  // Huffman-build workgroup
+typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline uint64_t arr_len(const ArrIn& a) {
   return a.n_dev ? min((uint64_t)*a.n_dev, a.n) : a.n;
@@ -1170,6 +1171,209 @@ __global__ __launch_bounds__(kThreads) void k_pack_huff(const EncArr* E, ArrWork
   if (threadIdx.x == 0 && words) atomicAdd(&w.huff_words[blockIdx.x % kWordParts], words);
 }
 
+// Byte arrays (temporal residuals, whose codes are nearly all a few bits
+// long) pack one chunk per wave: lane l takes the chunk's values
+// [l * RUN, l * RUN + RUN) with RUN = C / 64, the lanes' bit offsets come from
+// a wave scan, and the chunk image is assembled in the wave's own LDS slot, so
+// a chunk needs no workgroup barrier.  Chunk images, word counts and staging
+// slots are those of k_pack_huff.
+constexpr int kPackWaves = kThreads / kWave;
+constexpr bool pack_by_wave(int chunk_log2) { return chunk_log2 >= 6 && chunk_log2 <= 10; }
+
+// LDS accesses of this wave issued so far are complete; a compiler barrier too.
+__device__ inline void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// A lane's RUN bytes, packed four to a word (RUN < 4: one word), kept packed
+// until they are coded so that a prefetched chunk costs few registers.
+template <int RUN>
+struct ByteRun {
+  static constexpr int kWords = RUN >= 4 ? RUN / 4 : 1;
+  uint32_t w[kWords];
+  __device__ inline uint32_t at(int j) const { return (w[j >> 2] >> (8 * (j & 3))) & 255u; }
+};
+
+// One vector load (RUN = 4, 8 or 16; i0 + RUN <= n and v + i0 aligned to RUN
+// bytes).
+template <int RUN>
+__device__ inline void load_bytes_vec(const uint8_t* v, uint64_t i0, ByteRun<RUN>& b) {
+  if constexpr (RUN == 16) {
+    typedef const __attribute__((address_space(1))) U32x4* G4;
+    const U32x4 x = *(G4)(v + i0);
+    b.w[0] = x[0];
+    b.w[1] = x[1];
+    b.w[2] = x[2];
+    b.w[3] = x[3];
+  } else if constexpr (RUN == 8) {
+    typedef uint32_t U32x2 __attribute__((ext_vector_type(2)));
+    typedef const __attribute__((address_space(1))) U32x2* G2;
+    const U32x2 x = *(G2)(v + i0);
+    b.w[0] = x[0];
+    b.w[1] = x[1];
+  } else {
+    b.w[0] = *(const __attribute__((address_space(1))) uint32_t*)(v + i0);
+  }
+}
+
+// One load per byte, clamped to the last value (masked later).
+template <int RUN>
+__device__ inline void load_bytes_clamped(const uint8_t* v, uint64_t i0, uint64_t n,
+                                          ByteRun<RUN>& b) {
+  const __attribute__((address_space(1))) uint8_t* p = (const __attribute__((address_space(1))) uint8_t*)v;
+#pragma unroll
+  for (int q = 0; q < ByteRun<RUN>::kWords; q++) b.w[q] = 0;
+#pragma unroll
+  for (int j = 0; j < RUN; j++) b.w[j >> 2] |= (uint32_t)p[min(i0 + j, n - 1)] << (8 * (j & 3));
+}
+
+// The code of symbol s: the first kPackLcLds entries of the table are in LDS,
+// the rest (escaped values only) are read from the array's table.
+constexpr int kPackLcLds = 256;
+__device__ inline uint32_t code_of(uint32_t s, const uint32_t* lc_lds, const uint32_t* lc_glb) {
+  return s < (uint32_t)kPackLcLds ? lc_lds[s] : lc_glb[s];
+}
+
+// Packs chunk c of a byte array from this lane's bytes b; returns the chunk's
+// word count (written to cnta[c] by lane 0).
+template <int RUN>
+__device__ inline uint32_t pack_chunk_wave(uint32_t c, const ByteRun<RUN>& b, const uint32_t* esc,
+                                           uint64_t n, uint64_t C, const uint32_t* lc,
+                                           const uint32_t* lc_glb, uint32_t* buf, uint32_t* cnta,
+                                           uint32_t* pay, uint32_t slot, uint32_t* err) {
+  const uint32_t lane = (uint32_t)lane_id();
+  const uint64_t cend = min(n, (uint64_t)(c + 1) * C);
+  const uint64_t i0 = (uint64_t)c * C + lane * RUN;
+  uint32_t cl[RUN];
+  uint32_t bits = 0;
+  bool slow = false;  // an escaped value: its code and raw bits take the general path
+#pragma unroll
+  for (int j = 0; j < RUN; j++) {
+    const bool in = i0 + j < cend;
+    const uint32_t bj = b.at(j);
+    uint32_t code = 0;
+    int ex = 0;
+    if (in && bj == 255u) {
+      code = code_of((uint32_t)symbol_of(esc[i0 + j], &ex), lc, lc_glb);
+      slow = true;
+    } else {
+      code = lc[bj];
+    }
+    cl[j] = in ? code : 0u;
+    bits += (cl[j] >> 16) + (uint32_t)ex;
+  }
+  const uint32_t incl = wave_incl_scan(bits);
+  const uint32_t start = incl - bits;
+  const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+  const uint32_t nw = (total + 31u) >> 5;
+  // a chunk beyond its slot would mean the code and the data disagree:
+  // flagged, never written
+  if (nw > slot) {
+    if (lane == 0) {
+      atomicOr(err, kErrCorrupt);
+      cnta[c] = nw;
+    }
+    return nw;
+  }
+  for (uint32_t j = lane; j < nw; j += kWave) buf[j] = 0;
+  wave_lds_sync();
+  if (bits && !slow && bits <= 64) {
+    // the lane's codes in one register, placed MSB first at bit `start`:
+    // they touch at most three words
+    uint64_t str = 0;
+#pragma unroll
+    for (int j = 0; j < RUN; j++) str = (str << (cl[j] >> 16)) | (cl[j] & 0xFFFFu);
+    const uint64_t t = str << (64 - bits);
+    const uint32_t o = start & 31u, w0 = start >> 5;
+    atomicOr(&buf[w0], (uint32_t)(t >> (32 + o)));
+    if (o + bits > 32) atomicOr(&buf[w0 + 1], (uint32_t)(t >> o));
+    if (o + bits > 64) atomicOr(&buf[w0 + 2], (uint32_t)(t << (32 - o)));
+  } else if (bits) {
+    BitSink sk{0ull, (int)(start & 31u), start >> 5, buf};
+#pragma unroll
+    for (int j = 0; j < RUN; j++) {
+      if (i0 + j >= cend) break;
+      sk.push(cl[j] & 0xFFFFu, (int)(cl[j] >> 16));
+      if (b.at(j) == 255u) {
+        const uint64_t val = esc[i0 + j];
+        int ex = 0;
+        symbol_of(val, &ex);
+        if (ex) sk.push(val - (1ull << ex), ex);  // ex <= 31: the value is 32-bit
+      }
+    }
+    sk.flush();
+  }
+  wave_lds_sync();
+  uint32_t* dst = pay + (uint64_t)c * slot;
+  for (uint32_t j = lane; j < nw; j += kWave) dst[j] = buf[j];
+  if (lane == 0) cnta[c] = nw;
+  return nw;
+}
+
+// Workgroup lb of the nb packing byte array a: wave g = lb * kPackWaves + w
+// takes chunks g, g + G, ... (G = nb * kPackWaves).  Whole chunks of an array
+// whose bytes start 16-byte aligned load with vector loads, the next chunk's
+// while one is packed; the ragged last chunk (and every chunk otherwise) loads
+// byte by byte.
+template <int RUN>
+__global__ __launch_bounds__(kThreads) void k_pack_wave(const EncArr* E, ArrWork* W,
+                                                        const uint32_t* pre, int NA,
+                                                        int chunk_log2, uint32_t* cnt,
+                                                        uint32_t* stage, uint32_t slot,
+                                                        uint32_t* err) {
+  extern __shared__ uint32_t bufs[];
+  __shared__ uint32_t lc[kPackLcLds];
+  __shared__ unsigned long long wsum[kPackWaves];
+  const uint32_t a = array_of_block(pre, NA, blockIdx.x);
+  const uint32_t lb = blockIdx.x - pre[a], nb = pre[a + 1] - pre[a];
+  ArrWork& w = W[a];
+  if (!w.cand) return;
+  {
+    const int nsym = min(sym_bound(w.maxv) + 1, kPackLcLds);
+    for (int j = threadIdx.x; j < nsym; j += kThreads) lc[j] = w.lc[j];
+  }
+  __syncthreads();
+  const EncArr& e = E[a];
+  const uint64_t n = w.n;
+  const uint8_t* v = static_cast<const uint8_t*>(e.in.v);
+  const uint32_t* esc = e.in.esc;
+  uint32_t* cnta = cnt + e.cw0;
+  uint32_t* pay = stage + e.stage0;
+  uint32_t* buf = bufs + (uint64_t)wave_id() * slot;
+  const uint64_t C = 1ull << chunk_log2;
+  const uint32_t nchunks = (uint32_t)((n + C - 1) >> chunk_log2);
+  const uint32_t g = lb * kPackWaves + (uint32_t)wave_id(), G = nb * kPackWaves;
+  const uint64_t lane_off = (uint64_t)lane_id() * RUN;
+  const bool vec = RUN >= 4 && ((uintptr_t)v & 15u) == 0;
+  const uint32_t nfull = vec ? (uint32_t)(n >> chunk_log2) : 0u;
+  unsigned long long words = 0;
+  if constexpr (RUN >= 4) {
+    if (g < nfull) {
+      ByteRun<RUN> va, vb;
+      load_bytes_vec<RUN>(v, ((uint64_t)g << chunk_log2) + lane_off, va);
+      for (uint32_t c = g; c < nfull; c += 2 * G) {
+        load_bytes_vec<RUN>(v, ((uint64_t)min(c + G, nfull - 1) << chunk_log2) + lane_off, vb);
+        words += pack_chunk_wave<RUN>(c, va, esc, n, C, lc, w.lc, buf, cnta, pay, slot, err);
+        if (c + G >= nfull) break;
+        load_bytes_vec<RUN>(v, ((uint64_t)min(c + 2 * G, nfull - 1) << chunk_log2) + lane_off, va);
+        words += pack_chunk_wave<RUN>(c + G, vb, esc, n, C, lc, w.lc, buf, cnta, pay, slot, err);
+      }
+    }
+  }
+  // chunks from nfull on that belong to this wave
+  for (uint32_t c = nfull + (g + G - nfull % G) % G; c < nchunks; c += G) {
+    ByteRun<RUN> vt;
+    load_bytes_clamped<RUN>(v, ((uint64_t)c << chunk_log2) + lane_off, n, vt);
+    words += pack_chunk_wave<RUN>(c, vt, esc, n, C, lc, w.lc, buf, cnta, pay, slot, err);
+  }
+  if (lane_id() == 0) wsum[wave_id()] = words;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long tot = 0;
+#pragma unroll
+    for (int q = 0; q < kPackWaves; q++) tot += wsum[q];
+    if (tot) atomicAdd(&w.huff_words[blockIdx.x % kWordParts], tot);
+  }
+}
+
 __global__ __launch_bounds__(kHT) void k_layout(ArrWork* W, EncRec* recs, const EncRec rec0,
                                                 int R, uint8_t* out, uint64_t cap,
                                                 unsigned long long* offs,
@@ -1413,7 +1617,6 @@ constexpr int kRing = 16;
 typedef const __attribute__((address_space(1))) uint32_t* GWords;
 typedef __attribute__((address_space(1))) uint64_t* GOut64;
 typedef __attribute__((address_space(1))) uint32_t* GOut32;
-typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) U32x4* GOut128;
 
 // One chunk's bits, MSB first: buf holds nb valid bits; words [rpos, wpos)
@@ -1734,8 +1937,11 @@ uint32_t enc_hist_copies(uint64_t n) {
   const uint32_t c = (enc_hist_blocks(n) + 15) / 16;
   return c > (uint32_t)kHistCopies ? (uint32_t)kHistCopies : c;
 }
-uint32_t enc_chunk_blocks(uint64_t n, int chunk_log2) {
-  return gclamp((n + (1ull << chunk_log2) - 1) >> chunk_log2, 512);
+uint32_t enc_chunk_blocks(uint64_t n, int chunk_log2, bool bytes) {
+  // byte arrays pack one chunk per wave (k_pack_wave), others one per workgroup
+  const uint64_t nchunks = (n + (1ull << chunk_log2) - 1) >> chunk_log2;
+  return bytes && pack_by_wave(chunk_log2) ? gclamp((nchunks + kPackWaves - 1) / kPackWaves, 256)
+                                            : gclamp(nchunks, 512);
 }
 uint32_t enc_copy_blocks(uint64_t n, int chunk_log2) {
   return gclamp((n + (1ull << chunk_log2) - 1) >> chunk_log2, 256);
@@ -1773,7 +1979,20 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
     k_huff_codes<<<NA, kHT, 0, s>>>(L.arrs, work, X.huff_lens, X.huff_maxd, chunk_log2);
   }
   const uint32_t slot32 = enc_slot_words(false, chunk_log2), slot64 = enc_slot_words(true, chunk_log2);
-  {
+  if (L.all_bytes && pack_by_wave(chunk_log2)) {
+    // one chunk per wave: C / 64 values per lane
+    const size_t shm = (size_t)kPackWaves * slot32 * 4;
+    auto* kernel = k_pack_wave<16>;
+    switch (chunk_log2) {
+      case 6: kernel = k_pack_wave<1>; break;
+      case 7: kernel = k_pack_wave<2>; break;
+      case 8: kernel = k_pack_wave<4>; break;
+      case 9: kernel = k_pack_wave<8>; break;
+      default: break;
+    }
+    launch_timed("pack_huff", L.values * 6ull, kernel, L.chunk_blocks, kThreads, shm, s, L.arrs,
+                 work, pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, err);
+  } else {
     const size_t shm = (size_t)slot64 * 4;
     const uint32_t g = L.chunk_blocks;
     auto* kernel = k_pack_huff<1>;

@@ -409,7 +409,7 @@ lcp_status enc_add(lcp_plan_s* P, EncBuild& B, const ArrIn& in, uint64_t nb, int
   B.stage += enc_stage_words(nb, in.is64 != 0, P->chunk_log2);
   if (B.copies > P->hist_copies || B.cw > P->cw_cap || B.stage > P->stage_cap) return LCP_ERR_ARG;
   B.hb.push_back(enc_hist_blocks(nb));
-  B.cb.push_back(enc_chunk_blocks(nb, P->chunk_log2));
+  B.cb.push_back(enc_chunk_blocks(nb, P->chunk_log2, in.esc != nullptr));
   B.kb.push_back(enc_copy_blocks(nb, P->chunk_log2));
   B.fb.push_back(enc_fixed_blocks(nb));
   B.values += nb;
@@ -453,6 +453,8 @@ lcp_status enc_launch(lcp_plan_s* P, EncBuild& B, uint8_t* out, uint64_t cap, bo
   L.fixed_blocks = f;
   L.copy_blocks = k;
   L.values = B.values;
+  L.all_bytes = 1;
+  for (int a = 0; a < NA; a++) L.all_bytes &= P->earr_host[a].in.esc != nullptr ? 1 : 0;
   // A single record travels to the layout kernel as an argument; the array and
   // prefix tables are not uploaded again while the device holds the same bytes
   // (consecutive temporal frames of one size)

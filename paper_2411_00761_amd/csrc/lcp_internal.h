@@ -86,7 +86,7 @@ struct EncRec {
 // spread histogram copies, and its Huffman payload staging (words).
 uint32_t enc_hist_blocks(uint64_t n);
 uint32_t enc_hist_copies(uint64_t n);
-uint32_t enc_chunk_blocks(uint64_t n, int chunk_log2);
+uint32_t enc_chunk_blocks(uint64_t n, int chunk_log2, bool bytes);
 uint32_t enc_copy_blocks(uint64_t n, int chunk_log2);
 uint32_t enc_fixed_blocks(uint64_t n);
 uint32_t enc_slot_words(bool is64, int chunk_log2);
@@ -290,6 +290,7 @@ struct EncLaunch {
   int NA, R;
   uint32_t hist_blocks, chunk_blocks, fixed_blocks, copy_blocks;
   uint64_t values;  // sum of the arrays' lengths (bounds), for the kernel timer
+  int all_bytes;    // every array holds bytes with escapes (temporal residuals)
 };
 // Coding scratch of a launch set: a word count per chunk and the staging of
 // the Huffman payloads before they move into their records.
