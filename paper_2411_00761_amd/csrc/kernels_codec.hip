@@ -1178,6 +1178,10 @@ __global__ __launch_bounds__(kThreads) void k_pack_huff(const EncArr* E, ArrWork
 // a chunk needs no workgroup barrier.  Chunk images, word counts and staging
 // slots are those of k_pack_huff.
 constexpr int kPackWaves = kThreads / kWave;
+constexpr int kPackDepth = 4;  // whole chunks a wave has in flight
+// s_waitcnt immediate for vmcnt(0) alone (gfx9 encoding: vmcnt in bits 3:0
+// and 15:14, expcnt 6:4, lgkmcnt 11:8; the other counters at their maxima)
+constexpr int kWaitVm0 = 0x0F70;
 constexpr bool pack_by_wave(int chunk_log2) { return chunk_log2 >= 6 && chunk_log2 <= 10; }
 
 // LDS accesses of this wave issued so far are complete; a compiler barrier too.
@@ -1225,44 +1229,65 @@ __device__ inline void load_bytes_clamped(const uint8_t* v, uint64_t i0, uint64_
   for (int j = 0; j < RUN; j++) b.w[j >> 2] |= (uint32_t)p[min(i0 + j, n - 1)] << (8 * (j & 3));
 }
 
+static_assert(offsetof(ArrWork, lc) % 16 == 0 && sizeof(ArrWork) % 16 == 0,
+              "an array's code table is 16-byte aligned");
 // The code of symbol s: the first kPackLcLds entries of the table are in LDS,
 // the rest (escaped values only) are read from the array's table.
 constexpr int kPackLcLds = 256;
-__device__ inline uint32_t code_of(uint32_t s, const uint32_t* lc_lds, const uint32_t* lc_glb) {
+typedef const __attribute__((address_space(1))) uint32_t* GWordsIn;
+__device__ inline uint32_t code_of(uint32_t s, const uint32_t* lc_lds, GWordsIn lc_glb) {
   return s < (uint32_t)kPackLcLds ? lc_lds[s] : lc_glb[s];
 }
 
+// Inclusive sum over the wave's 64 lanes with DPP row shifts and row
+// broadcasts (no LDS round trips).
+__device__ inline uint32_t wave_incl_sum_dpp(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, false);  // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return v;
+}
+
 // Packs chunk c of a byte array from this lane's bytes b; returns the chunk's
-// word count (written to cnta[c] by lane 0).
-template <int RUN>
-__device__ inline uint32_t pack_chunk_wave(uint32_t c, const ByteRun<RUN>& b, const uint32_t* esc,
+// word count (written to cnta[c] by lane 0).  FULL: the chunk has all C values.
+template <int RUN, bool FULL>
+__device__ inline uint32_t pack_chunk_wave(uint32_t c, const ByteRun<RUN>& b, GWordsIn esc,
                                            uint64_t n, uint64_t C, const uint32_t* lc,
-                                           const uint32_t* lc_glb, uint32_t* buf, uint32_t* cnta,
+                                           GWordsIn lc_glb, uint32_t* buf, uint32_t* cnta,
                                            uint32_t* pay, uint32_t slot, uint32_t* err) {
   const uint32_t lane = (uint32_t)lane_id();
-  const uint64_t cend = min(n, (uint64_t)(c + 1) * C);
+  const uint64_t cend = FULL ? (uint64_t)(c + 1) * C : min(n, (uint64_t)(c + 1) * C);
   const uint64_t i0 = (uint64_t)c * C + lane * RUN;
   uint32_t cl[RUN];
   uint32_t bits = 0;
   bool slow = false;  // an escaped value: its code and raw bits take the general path
 #pragma unroll
-  for (int j = 0; j < RUN; j++) {
-    const bool in = i0 + j < cend;
-    const uint32_t bj = b.at(j);
-    uint32_t code = 0;
-    int ex = 0;
-    if (in && bj == 255u) {
-      code = code_of((uint32_t)symbol_of(esc[i0 + j], &ex), lc, lc_glb);
-      slow = true;
-    } else {
-      code = lc[bj];
+  for (int j = 0; j < RUN; j++) slow |= (FULL || i0 + j < cend) && b.at(j) == 255u;
+  if (__ballot(slow) == 0) {
+#pragma unroll
+    for (int j = 0; j < RUN; j++) {
+      cl[j] = (FULL || i0 + j < cend) ? lc[b.at(j)] : 0u;
+      bits += cl[j] >> 16;
     }
-    cl[j] = in ? code : 0u;
-    bits += (cl[j] >> 16) + (uint32_t)ex;
+  } else {
+#pragma unroll
+    for (int j = 0; j < RUN; j++) {
+      const bool in = FULL || i0 + j < cend;
+      const uint32_t bj = b.at(j);
+      uint32_t code = 0;
+      int ex = 0;
+      if (in && bj == 255u) code = code_of((uint32_t)symbol_of(esc[i0 + j], &ex), lc, lc_glb);
+      else code = lc[bj];
+      cl[j] = in ? code : 0u;
+      bits += (cl[j] >> 16) + (uint32_t)ex;
+    }
   }
-  const uint32_t incl = wave_incl_scan(bits);
+  const uint32_t incl = wave_incl_sum_dpp(bits);
   const uint32_t start = incl - bits;
-  const uint32_t total = (uint32_t)__shfl((int)incl, kWave - 1, kWave);
+  const uint32_t total = (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
   const uint32_t nw = (total + 31u) >> 5;
   // a chunk beyond its slot would mean the code and the data disagree:
   // flagged, never written
@@ -1290,7 +1315,7 @@ __device__ inline uint32_t pack_chunk_wave(uint32_t c, const ByteRun<RUN>& b, co
     BitSink sk{0ull, (int)(start & 31u), start >> 5, buf};
 #pragma unroll
     for (int j = 0; j < RUN; j++) {
-      if (i0 + j >= cend) break;
+      if (!FULL && i0 + j >= cend) break;
       sk.push(cl[j] & 0xFFFFu, (int)(cl[j] >> 16));
       if (b.at(j) == 255u) {
         const uint64_t val = esc[i0 + j];
@@ -1325,36 +1350,63 @@ __global__ __launch_bounds__(kThreads) void k_pack_wave(const EncArr* E, ArrWork
   const uint32_t a = array_of_block(pre, NA, blockIdx.x);
   const uint32_t lb = blockIdx.x - pre[a], nb = pre[a + 1] - pre[a];
   ArrWork& w = W[a];
-  if (!w.cand) return;
-  {
-    const int nsym = min(sym_bound(w.maxv) + 1, kPackLcLds);
-    for (int j = threadIdx.x; j < nsym; j += kThreads) lc[j] = w.lc[j];
-  }
-  __syncthreads();
   const EncArr& e = E[a];
+  if (!w.cand) return;
   const uint64_t n = w.n;
   const uint8_t* v = static_cast<const uint8_t*>(e.in.v);
-  const uint32_t* esc = e.in.esc;
+  GWordsIn esc = (GWordsIn)e.in.esc;
+  GWordsIn lc_glb = (GWordsIn)w.lc;
   uint32_t* cnta = cnt + e.cw0;
   uint32_t* pay = stage + e.stage0;
-  uint32_t* buf = bufs + (uint64_t)wave_id() * slot;
+  // the wave index is uniform: loops over chunks stay scalar
+  const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane(wave_id());
+  uint32_t* buf = bufs + (uint64_t)wv * slot;
   const uint64_t C = 1ull << chunk_log2;
   const uint32_t nchunks = (uint32_t)((n + C - 1) >> chunk_log2);
-  const uint32_t g = lb * kPackWaves + (uint32_t)wave_id(), G = nb * kPackWaves;
+  const uint32_t g = lb * kPackWaves + wv, G = nb * kPackWaves;
   const uint64_t lane_off = (uint64_t)lane_id() * RUN;
   const bool vec = RUN >= 4 && ((uintptr_t)v & 15u) == 0;
   const uint32_t nfull = vec ? (uint32_t)(n >> chunk_log2) : 0u;
   unsigned long long words = 0;
+  // the code table's entries (one load per thread), then the wave's first
+  // kPackDepth whole chunks, all in flight together; later rounds load their
+  // kPackDepth chunks at once too, so a round waits for memory once
+  // (the loads are unconditional, so that waiting for the table's does not
+  // wait for the chunks': a wave without whole chunks reads the table's words)
+  const uint32_t nsym = min((uint32_t)sym_bound(w.maxv) + 1u, (uint32_t)kPackLcLds);
+  const uint32_t lc_t = lc_glb[min((uint32_t)threadIdx.x, nsym - 1u)];
+  ByteRun<RUN> q[kPackDepth];
+  const bool deep = RUN >= 4 && g < nfull;
   if constexpr (RUN >= 4) {
-    if (g < nfull) {
-      ByteRun<RUN> va, vb;
-      load_bytes_vec<RUN>(v, ((uint64_t)g << chunk_log2) + lane_off, va);
-      for (uint32_t c = g; c < nfull; c += 2 * G) {
-        load_bytes_vec<RUN>(v, ((uint64_t)min(c + G, nfull - 1) << chunk_log2) + lane_off, vb);
-        words += pack_chunk_wave<RUN>(c, va, esc, n, C, lc, w.lc, buf, cnta, pay, slot, err);
-        if (c + G >= nfull) break;
-        load_bytes_vec<RUN>(v, ((uint64_t)min(c + 2 * G, nfull - 1) << chunk_log2) + lane_off, va);
-        words += pack_chunk_wave<RUN>(c + G, vb, esc, n, C, lc, w.lc, buf, cnta, pay, slot, err);
+    const uint8_t* src = deep ? v : reinterpret_cast<const uint8_t*>(w.lc);
+#pragma unroll
+    for (int k = 0; k < kPackDepth; k++)
+      load_bytes_vec<RUN>(src, deep ? ((uint64_t)min(g + k * G, nfull - 1) << chunk_log2) + lane_off
+                                    : lane_off,
+                          q[k]);
+  }
+  if (threadIdx.x < nsym) lc[threadIdx.x] = lc_t;
+  __syncthreads();
+  if constexpr (RUN >= 4) {
+    if (deep) {
+      for (uint32_t c0 = g;;) {
+        // the round's chunks are in (and the last round's stores done): one
+        // wait, where the compiler would otherwise wait before each chunk for
+        // the stores of the one before, which share the loads' counter
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+#pragma unroll
+        for (int k = 0; k < kPackDepth; k++) {
+          const uint32_t c = c0 + k * G;
+          if (c < nfull)
+            words += pack_chunk_wave<RUN, true>(c, q[k], esc, n, C, lc, lc_glb, buf, cnta, pay,
+                                                slot, err);
+        }
+        c0 += kPackDepth * G;
+        if (c0 >= nfull) break;
+#pragma unroll
+        for (int k = 0; k < kPackDepth; k++)
+          load_bytes_vec<RUN>(v, ((uint64_t)min(c0 + k * G, nfull - 1) << chunk_log2) + lane_off,
+                              q[k]);
       }
     }
   }
@@ -1362,14 +1414,14 @@ __global__ __launch_bounds__(kThreads) void k_pack_wave(const EncArr* E, ArrWork
   for (uint32_t c = nfull + (g + G - nfull % G) % G; c < nchunks; c += G) {
     ByteRun<RUN> vt;
     load_bytes_clamped<RUN>(v, ((uint64_t)c << chunk_log2) + lane_off, n, vt);
-    words += pack_chunk_wave<RUN>(c, vt, esc, n, C, lc, w.lc, buf, cnta, pay, slot, err);
+    words += pack_chunk_wave<RUN, false>(c, vt, esc, n, C, lc, lc_glb, buf, cnta, pay, slot, err);
   }
-  if (lane_id() == 0) wsum[wave_id()] = words;
+  if (lane_id() == 0) wsum[wv] = words;
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long tot = 0;
 #pragma unroll
-    for (int q = 0; q < kPackWaves; q++) tot += wsum[q];
+    for (int k = 0; k < kPackWaves; k++) tot += wsum[k];
     if (tot) atomicAdd(&w.huff_words[blockIdx.x % kWordParts], tot);
   }
 }
