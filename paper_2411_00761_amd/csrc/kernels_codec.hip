@@ -1231,13 +1231,17 @@ __device__ inline void load_bytes_clamped(const uint8_t* v, uint64_t i0, uint64_
 
 static_assert(offsetof(ArrWork, lc) % 16 == 0 && sizeof(ArrWork) % 16 == 0,
               "an array's code table is 16-byte aligned");
-// The code of symbol s: the first kPackLcLds entries of the table are in LDS,
-// the rest (escaped values only) are read from the array's table.
+// The code of symbol s as length | code << 16 (the table's halves swapped, so
+// that the length is the low bits a 64-bit shift takes): the first kPackLcLds
+// entries are in LDS, the rest (escaped values only) are read from the table.
 constexpr int kPackLcLds = 256;
 typedef const __attribute__((address_space(1))) uint32_t* GWordsIn;
+__device__ inline uint32_t swap_halves(uint32_t x) { return (x >> 16) | (x << 16); }
 __device__ inline uint32_t code_of(uint32_t s, const uint32_t* lc_lds, GWordsIn lc_glb) {
-  return s < (uint32_t)kPackLcLds ? lc_lds[s] : lc_glb[s];
+  return s < (uint32_t)kPackLcLds ? lc_lds[s] : swap_halves(lc_glb[s]);
 }
+// Non-zero iff one of the word's four bytes is 255.
+__device__ inline uint32_t has_ff(uint32_t w) { return ((w & 0x7F7F7F7Fu) + 0x01010101u) & w & 0x80808080u; }
 
 // Inclusive sum over the wave's 64 lanes with DPP row shifts and row
 // broadcasts (no LDS round trips).
@@ -1261,16 +1265,19 @@ __device__ inline uint32_t pack_chunk_wave(uint32_t c, const ByteRun<RUN>& b, GW
   const uint32_t lane = (uint32_t)lane_id();
   const uint64_t cend = FULL ? (uint64_t)(c + 1) * C : min(n, (uint64_t)(c + 1) * C);
   const uint64_t i0 = (uint64_t)c * C + lane * RUN;
-  uint32_t cl[RUN];
+  uint32_t cl[RUN];  // length | code << 16
   uint32_t bits = 0;
-  bool slow = false;  // an escaped value: its code and raw bits take the general path
+  // an escaped value (byte 255) sends the lane's codes and raw bits down the
+  // general path; the check is per word (unused bytes of a short run are 0)
+  uint32_t ff = 0;
 #pragma unroll
-  for (int j = 0; j < RUN; j++) slow |= (FULL || i0 + j < cend) && b.at(j) == 255u;
+  for (int q = 0; q < ByteRun<RUN>::kWords; q++) ff |= has_ff(b.w[q]);
+  const bool slow = ff != 0;
   if (__ballot(slow) == 0) {
 #pragma unroll
     for (int j = 0; j < RUN; j++) {
       cl[j] = (FULL || i0 + j < cend) ? lc[b.at(j)] : 0u;
-      bits += cl[j] >> 16;
+      bits += cl[j] & 0xFFu;
     }
   } else {
 #pragma unroll
@@ -1282,7 +1289,7 @@ __device__ inline uint32_t pack_chunk_wave(uint32_t c, const ByteRun<RUN>& b, GW
       if (in && bj == 255u) code = code_of((uint32_t)symbol_of(esc[i0 + j], &ex), lc, lc_glb);
       else code = lc[bj];
       cl[j] = in ? code : 0u;
-      bits += (cl[j] >> 16) + (uint32_t)ex;
+      bits += (cl[j] & 0xFFu) + (uint32_t)ex;
     }
   }
   const uint32_t incl = wave_incl_sum_dpp(bits);
@@ -1305,7 +1312,7 @@ __device__ inline uint32_t pack_chunk_wave(uint32_t c, const ByteRun<RUN>& b, GW
     // they touch at most three words
     uint64_t str = 0;
 #pragma unroll
-    for (int j = 0; j < RUN; j++) str = (str << (cl[j] >> 16)) | (cl[j] & 0xFFFFu);
+    for (int j = 0; j < RUN; j++) str = (str << (cl[j] & 63u)) | (cl[j] >> 16);
     const uint64_t t = str << (64 - bits);
     const uint32_t o = start & 31u, w0 = start >> 5;
     atomicOr(&buf[w0], (uint32_t)(t >> (32 + o)));
@@ -1316,7 +1323,7 @@ __device__ inline uint32_t pack_chunk_wave(uint32_t c, const ByteRun<RUN>& b, GW
 #pragma unroll
     for (int j = 0; j < RUN; j++) {
       if (!FULL && i0 + j >= cend) break;
-      sk.push(cl[j] & 0xFFFFu, (int)(cl[j] >> 16));
+      sk.push(cl[j] >> 16, (int)(cl[j] & 0xFFu));
       if (b.at(j) == 255u) {
         const uint64_t val = esc[i0 + j];
         int ex = 0;
@@ -1385,7 +1392,7 @@ __global__ __launch_bounds__(kThreads) void k_pack_wave(const EncArr* E, ArrWork
                                     : lane_off,
                           q[k]);
   }
-  if (threadIdx.x < nsym) lc[threadIdx.x] = lc_t;
+  if (threadIdx.x < nsym) lc[threadIdx.x] = swap_halves(lc_t);
   __syncthreads();
   if constexpr (RUN >= 4) {
     if (deep) {
