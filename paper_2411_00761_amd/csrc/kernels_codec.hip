@@ -46,6 +46,15 @@ __device__ inline uint32_t array_of_block(const uint32_t* prefix, int A, uint32_
   }
   return (uint32_t)lo;
 }
+// The same for A <= 8 with the prefixes read together (one round of loads, not
+// a chain): the number of a in [1, A) with prefix[a] <= b.
+__device__ inline uint32_t array_of_block_few(const uint32_t* prefix, int A, uint32_t b) {
+  if (A > 8) return array_of_block(prefix, A, b);
+  uint32_t a = 0;
+#pragma unroll
+  for (int i = 1; i < 8; i++) a += (i < A && prefix[i] <= b) ? 1u : 0u;
+  return a;
+}
 
 // ------------------------------------------------------------------ histogram
 // Each workgroup counts its share of one array in LDS (wave_hist_add: the
@@ -1235,6 +1244,7 @@ static_assert(offsetof(ArrWork, lc) % 16 == 0 && sizeof(ArrWork) % 16 == 0,
 // that the length is the low bits a 64-bit shift takes): the first kPackLcLds
 // entries are in LDS, the rest (escaped values only) are read from the table.
 constexpr int kPackLcLds = 256;
+static_assert(kPackLcLds == kThreads && kAlphabet >= kPackLcLds, "one table entry per thread");
 typedef const __attribute__((address_space(1))) uint32_t* GWordsIn;
 __device__ inline uint32_t swap_halves(uint32_t x) { return (x >> 16) | (x << 16); }
 __device__ inline uint32_t code_of(uint32_t s, const uint32_t* lc_lds, GWordsIn lc_glb) {
@@ -1354,10 +1364,13 @@ __global__ __launch_bounds__(kThreads) void k_pack_wave(const EncArr* E, ArrWork
   extern __shared__ uint32_t bufs[];
   __shared__ uint32_t lc[kPackLcLds];
   __shared__ unsigned long long wsum[kPackWaves];
-  const uint32_t a = array_of_block(pre, NA, blockIdx.x);
+  const uint32_t a = array_of_block_few(pre, NA, blockIdx.x);
   const uint32_t lb = blockIdx.x - pre[a], nb = pre[a + 1] - pre[a];
   ArrWork& w = W[a];
   const EncArr& e = E[a];
+  // the table's first kPackLcLds entries, requested with the array's fields
+  // (entries past the largest value's symbol are never looked up)
+  const uint32_t lc_t = ((GWordsIn)w.lc)[threadIdx.x];
   if (!w.cand) return;
   const uint64_t n = w.n;
   const uint8_t* v = static_cast<const uint8_t*>(e.in.v);
@@ -1375,13 +1388,11 @@ __global__ __launch_bounds__(kThreads) void k_pack_wave(const EncArr* E, ArrWork
   const bool vec = RUN >= 4 && ((uintptr_t)v & 15u) == 0;
   const uint32_t nfull = vec ? (uint32_t)(n >> chunk_log2) : 0u;
   unsigned long long words = 0;
-  // the code table's entries (one load per thread), then the wave's first
-  // kPackDepth whole chunks, all in flight together; later rounds load their
-  // kPackDepth chunks at once too, so a round waits for memory once
-  // (the loads are unconditional, so that waiting for the table's does not
-  // wait for the chunks': a wave without whole chunks reads the table's words)
-  const uint32_t nsym = min((uint32_t)sym_bound(w.maxv) + 1u, (uint32_t)kPackLcLds);
-  const uint32_t lc_t = lc_glb[min((uint32_t)threadIdx.x, nsym - 1u)];
+  // the wave's first kPackDepth whole chunks are in flight with the code
+  // table's entries; later rounds load their kPackDepth chunks at once too, so
+  // a round waits for memory once (the loads are unconditional, so that
+  // waiting for the table's does not wait for the chunks': a wave without
+  // whole chunks reads the table's words)
   ByteRun<RUN> q[kPackDepth];
   const bool deep = RUN >= 4 && g < nfull;
   if constexpr (RUN >= 4) {
@@ -1392,7 +1403,7 @@ __global__ __launch_bounds__(kThreads) void k_pack_wave(const EncArr* E, ArrWork
                                     : lane_off,
                           q[k]);
   }
-  if (threadIdx.x < nsym) lc[threadIdx.x] = swap_halves(lc_t);
+  lc[threadIdx.x] = swap_halves(lc_t);
   __syncthreads();
   if constexpr (RUN >= 4) {
     if (deep) {
