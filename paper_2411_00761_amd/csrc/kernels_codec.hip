@@ -1480,7 +1480,7 @@ __device__ inline void copy_huff_block(const EncArr* E, const ArrWork* W, const 
   const uint32_t per = (nchunks + nb - 1) / nb;
   const uint32_t c0 = min(nchunks, lb * per), c1 = min(nchunks, c0 + per);
   if (c0 >= c1) return;
-  constexpr int kPf = 8;
+  constexpr int kPf = 16;  // one round of loads covers 4096 chunks
   unsigned long long part = 0;
   for (uint32_t j0 = 0; j0 < c0; j0 += kThreads * kPf) {
     uint32_t v[kPf];
@@ -1505,16 +1505,28 @@ __device__ inline void copy_huff_block(const EncArr* E, const ArrWork* W, const 
       c_end[threadIdx.x] = (uint32_t)incl;
     }
     __syncthreads();
+    // wave w copies the tile's chunks w, w + kPackWaves, ...: the first 64
+    // words of kCopyAhead chunks are loaded together, longer chunks finish
+    // word by word
     uint32_t* d = dpay + base;
-    for (uint32_t j = threadIdx.x; j < (uint32_t)tot; j += kThreads) {
-      uint32_t lo = 0, hi = m - 1;  // first chunk of the tile ending after word j
-      while (lo < hi) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (c_end[mid] > j) hi = mid;
-        else lo = mid + 1;
+    const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane(wave_id()), lane = lane_id();
+    constexpr int kCopyAhead = 4;
+    for (uint32_t i0 = wv; i0 < m; i0 += kPackWaves * kCopyAhead) {
+      uint32_t val[kCopyAhead], s0[kCopyAhead], nw[kCopyAhead];
+#pragma unroll
+      for (int q = 0; q < kCopyAhead; q++) {
+        const uint32_t i = i0 + q * kPackWaves;
+        s0[q] = i < m && i ? c_end[i - 1] : 0u;
+        nw[q] = i < m ? c_end[i] - s0[q] : 0u;
+        val[q] = lane < nw[q] ? pay[(uint64_t)(t0 + i) * slot + lane] : 0u;
       }
-      const uint32_t start = lo ? c_end[lo - 1] : 0u;
-      d[j] = pay[(uint64_t)(t0 + lo) * slot + (j - start)];
+#pragma unroll
+      for (int q = 0; q < kCopyAhead; q++) {
+        const uint32_t i = i0 + q * kPackWaves;
+        if (lane < nw[q]) d[s0[q] + lane] = val[q];
+        for (uint32_t j = kWave + lane; j < nw[q]; j += kWave)
+          d[s0[q] + j] = pay[(uint64_t)(t0 + i) * slot + j];
+      }
     }
     base += tot;
     __syncthreads();
@@ -1531,12 +1543,12 @@ __global__ __launch_bounds__(kThreads) void k_emit(const EncArr* E, const ArrWor
                                                    uint32_t slot64, uint8_t* out,
                                                    const uint32_t* err) {
   if (blockIdx.x < fixed_blocks) {
-    const uint32_t a = array_of_block(pre_fixed, NA, blockIdx.x);
+    const uint32_t a = array_of_block_few(pre_fixed, NA, blockIdx.x);
     pack_fixed_block(E, W, recs, a, blockIdx.x - pre_fixed[a], pre_fixed[a + 1] - pre_fixed[a],
                      out, err);
   } else {
     const uint32_t b = blockIdx.x - fixed_blocks;
-    const uint32_t a = array_of_block(pre_copy, NA, b);
+    const uint32_t a = array_of_block_few(pre_copy, NA, b);
     copy_huff_block(E, W, recs, a, b - pre_copy[a], pre_copy[a + 1] - pre_copy[a], cnt, stage,
                     slot32, slot64, out, err);
   }
