@@ -630,14 +630,17 @@ __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* p
   __shared__ unsigned long long red[1];
   uint8_t* smb = reinterpret_cast<uint8_t*>(sm64);
   const int a = blockIdx.x, t = threadIdx.x;
-  const EncArr& e = E[a];
   ArrWork& w = W[a];
+  // the array's fields, read once: the stores below could alias them, and
+  // each reread would wait for all loads in flight
+  const uint32_t copies = E[a].copies, copy0 = E[a].copy0;
+  const uint64_t n = arr_len(E[a].in);
   // largest value over the copies (and clear them)
   unsigned long long mx = 0;
-  for (uint32_t c = t; c < e.copies; c += kHT) {
-    const unsigned long long v = part_max[e.copy0 + c];
+  for (uint32_t c = t; c < copies; c += kHT) {
+    const unsigned long long v = part_max[copy0 + c];
     mx = v > mx ? v : mx;
-    part_max[e.copy0 + c] = 0;
+    part_max[copy0 + c] = 0;
   }
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) {
@@ -648,13 +651,12 @@ __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* p
   __syncthreads();
   mx = 0;
   for (int j = 0; j < kHT / kWave; j++) mx = smx[j] > mx ? smx[j] : mx;
-  const uint64_t n = arr_len(e.in);
   const int top = n ? sym_bound(mx) : -1;
   // only symbols up to the largest value's can occur; every loop below stops
   // there (entries past it are never read)
   const int nsym = top + 1;
   uint32_t cnt[kPer];
-  uint32_t* src = part + (uint64_t)e.copy0 * kAlphabet;
+  uint32_t* src = part + (uint64_t)copy0 * kAlphabet;
 #pragma unroll
   for (int j = 0; j < kPer; j++) {
     const int s = t + kHT * j;
@@ -663,11 +665,11 @@ __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* p
       uint32_t x[kHistCopies];
 #pragma unroll
       for (int c = 0; c < kHistCopies; c++)
-        x[c] = (uint32_t)c < e.copies ? src[(uint64_t)c * kAlphabet + s] : 0u;
+        x[c] = (uint32_t)c < copies ? src[(uint64_t)c * kAlphabet + s] : 0u;
 #pragma unroll
       for (int c = 0; c < kHistCopies; c++) {
         v += x[c];
-        if ((uint32_t)c < e.copies) src[(uint64_t)c * kAlphabet + s] = 0;
+        if ((uint32_t)c < copies) src[(uint64_t)c * kAlphabet + s] = 0;
       }
       w.hist[s] = v;
     }
