@@ -36,6 +36,9 @@ __device__ inline uint64_t shfl_xor_u64(uint64_t v, int m) {
   return ((uint64_t)hi << 32) | lo;
 }
 
+// LDS accesses of this wave issued so far are complete; a compiler barrier too.
+__device__ inline void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
 // Array of workgroup b: the largest a < A with prefix[a] <= b.
 __device__ inline uint32_t array_of_block(const uint32_t* prefix, int A, uint32_t b) {
   int lo = 0, hi = A - 1;  // largest a with prefix[a] <= b
@@ -430,19 +433,28 @@ __device__ inline void empty_codes(ArrWork& w) {
 // symbol).  Same lengths and codes as the workgroup build.  Counts are halved
 // (c -> ceil(c / 2)) until the longest code fits.  Writes lc, table, U, L;
 // returns this lane's symbol's code length.
-__device__ inline uint64_t lane_sort64(uint64_t key) {
-  const int lane = lane_id();
-#pragma unroll
-  for (int size = 2; size <= kWave; size <<= 1) {
-#pragma unroll
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      const uint64_t x = shfl_xor_u64(key, stride);
-      const bool asc = (lane & size) == 0;
-      const bool lower = (lane & stride) == 0;
-      key = (lower == asc) ? (x < key ? x : key) : (x > key ? x : key);
-    }
+__device__ inline uint32_t lane_u32(uint32_t v, uint32_t l);
+
+// Lane i receives the i-th smallest key of the lanes in `used` (their keys
+// distinct), lanes from popc(used) on the other lanes' keys in lane order.
+// Each used lane's rank counts the used keys below its own, taken one lane at
+// a time by broadcast (used lanes are few: no shuffle network), and the keys
+// are placed by rank through the wave's 64-entry LDS scratch.
+__device__ inline uint64_t lane_sort_used(uint64_t key, uint64_t used, uint64_t* scratch) {
+  const uint32_t lane = (uint32_t)lane_id();
+  uint32_t r = 0;
+  for (uint64_t m = used; m; m &= m - 1) {
+    const uint32_t j = (uint32_t)__builtin_ctzll(m);
+    const uint64_t kj = ((uint64_t)lane_u32((uint32_t)(key >> 32), j) << 32) | lane_u32((uint32_t)key, j);
+    r += kj < key ? 1u : 0u;
   }
-  return key;
+  const uint32_t U = (uint32_t)__popcll(used);
+  const uint32_t rank = (used >> lane) & 1 ? r : U + (uint32_t)__popcll(~used & lanemask_lt());
+  scratch[rank] = key;
+  wave_lds_sync();
+  const uint64_t out = scratch[lane];
+  wave_lds_sync();
+  return out;
 }
 
 __device__ inline uint32_t lane_u32(uint32_t v, uint32_t l) {
@@ -451,7 +463,7 @@ __device__ inline uint32_t lane_u32(uint32_t v, uint32_t l) {
 
 // Lengths of one wave's code with `h` halvings (c -> ceil(c / 2), h times) of
 // lane s's count; returns the longest, sets this lane's length (0 if unused).
-__device__ uint32_t small_lengths(uint32_t count, int h, uint32_t* len_out) {
+__device__ uint32_t small_lengths(uint32_t count, int h, uint32_t* len_out, uint64_t* scratch) {
   const uint32_t lane = (uint32_t)lane_id();
   const uint64_t used = __ballot(count != 0);
   const uint32_t U = (uint32_t)__popcll(used);
@@ -462,7 +474,7 @@ __device__ uint32_t small_lengths(uint32_t count, int h, uint32_t* len_out) {
   uint32_t c = count;
   for (int j = 0; j < h && c > 1; j++) c = (c + 1u) >> 1;
   // leaves in (count, symbol) order; unused symbols sort last
-  const uint64_t key = lane_sort64(c ? (((uint64_t)c << 13) | lane) : ~0ull);
+  const uint64_t key = lane_sort_used(c ? (((uint64_t)c << 13) | lane) : ~0ull, used, scratch);
   const uint32_t lw = (uint32_t)(key >> 13);   // leaf weight (lane i = leaf i)
   const uint32_t ls = (uint32_t)(key & 0x1FFFu);
   uint32_t iw = 0;     // internal node weights (lane k = internal node k)
@@ -521,15 +533,13 @@ __device__ uint32_t small_lengths(uint32_t count, int h, uint32_t* len_out) {
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) md = max(md, (uint32_t)__shfl_xor((int)md, d, kWave));
   // lengths back to symbol lanes: leaf i carries symbol ls
-  const uint64_t k2 = lane_sort64(lane < U ? (((uint64_t)ls << 8) | ldep) : ~0ull);
-  const uint32_t s2 = (uint32_t)(k2 >> 8), d2 = (uint32_t)(k2 & 0xFFu);
-  // lane s now holds the s-th used symbol in ascending order
-  uint32_t len = 0;
-  for (uint32_t u = 0; u < U; u++) {
-    const uint32_t su = lane_u32(s2, u), du = lane_u32(d2, u);
-    if (lane == su) len = du;
-  }
-  *len_out = len;
+  uint32_t* s32 = reinterpret_cast<uint32_t*>(scratch);
+  s32[lane] = 0;
+  wave_lds_sync();
+  if (lane < U) s32[ls] = ldep;
+  wave_lds_sync();
+  *len_out = s32[lane];
+  wave_lds_sync();
   return md;
 }
 
@@ -696,7 +706,8 @@ __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* p
     __syncthreads();
     const uint32_t c = s_cnt[lane_id()];
     uint32_t len;
-    const uint32_t md = small_lengths(c, wave_id(), &len);
+    uint64_t* scratch = sm64 + wave_id() * kWave;  // the small path leaves sm64 free
+    const uint32_t md = small_lengths(c, wave_id(), &len, scratch);
     if (lane_id() == 0) s_md[wave_id()] = md;
     __syncthreads();
     int pick = -1;
@@ -705,7 +716,7 @@ __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* p
     if (pick < 0 && wave_id() == 0) {  // more halvings than waves: one at a time
       uint32_t mdh = kMaxLen + 1;
       for (int h = kHT / kWave; h < kHalvings && mdh > (uint32_t)kMaxLen; h++)
-        mdh = small_lengths(c, h, &len);
+        mdh = small_lengths(c, h, &len, scratch);
       small_codes(w, c, len, mdh, maxd);
       finish_wave(w, (unsigned long long)c * len, (uint32_t)__popcll(__ballot(c != 0)), n, mx,
                   chunk_log2);
@@ -1195,8 +1206,6 @@ constexpr int kPackDepth = 4;  // whole chunks a wave has in flight
 constexpr int kWaitVm0 = 0x0F70;
 constexpr bool pack_by_wave(int chunk_log2) { return chunk_log2 >= 6 && chunk_log2 <= 10; }
 
-// LDS accesses of this wave issued so far are complete; a compiler barrier too.
-__device__ inline void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 // A lane's RUN bytes, packed four to a word (RUN < 4: one word), kept packed
 // until they are coded so that a prefetched chunk costs few registers.
