@@ -898,6 +898,40 @@ __device__ inline void write_header(const RecHdr& h, uint64_t B, uint64_t size, 
   }
 }
 
+// An array's coder: Huffman when it is a candidate and strictly shorter than
+// fixed length, which wins ties.
+struct ArrChoice {
+  uint32_t coder, param, U, wd;
+  uint64_t n, nbytes;
+};
+__device__ inline ArrChoice choose_coder(const ArrWork& w) {
+  ArrChoice c;
+  c.n = w.n;
+  const uint64_t mv = w.maxv;
+  const uint32_t L = w.L, cand = w.cand, nc = w.nchunks, U = w.U;
+  uint64_t hw = 0;
+#pragma unroll
+  for (int q = 0; q < kWordParts; q++) hw += w.huff_words[q];
+  c.wd = (uint32_t)bitwidth64(mv);
+  const uint64_t fixed = 4 * ((c.n * (uint64_t)c.wd + 31) / 32);
+  const uint64_t huff = 4ull * U + 4ull * nc + 4ull * hw;
+  const bool use_h = cand && huff < fixed;
+  c.coder = use_h ? 1u : 0u;
+  c.param = use_h ? L : c.wd;
+  c.U = use_h ? U : 0u;
+  c.nbytes = use_h ? huff : fixed;
+  return c;
+}
+
+__device__ inline void write_dir(uint8_t* o, int F, int a, const ArrChoice& c, uint64_t aoff) {
+  const uint64_t d = (uint64_t)kHdrBytes + 8ull * F + (uint64_t)kDirBytes * a;
+  put32(o, d, c.coder | (c.param << 8));
+  put32(o, d + 4, c.U);
+  put64(o, d + 8, c.n);
+  put64(o, d + 16, aoff);
+  put64(o, d + 24, c.nbytes);
+}
+
 template <int NT>
 __device__ void layout_records(ArrWork* W, EncRec* recs, const EncRec& rec0, int R, uint8_t* out,
                                uint64_t cap, unsigned long long* offs,
@@ -929,29 +963,14 @@ __device__ void layout_records(ArrWork* W, EncRec* recs, const EncRec& rec0, int
     }
     __syncthreads();
     const bool av = j < kLayRecs && base + j < R && a < s_A[j];
-    uint32_t coder = 0, param = 0, U = 0;
-    uint64_t n = 0, nbytes = 0;
+    ArrChoice ch{};
     if (av) {
       ArrWork& w = W[s_a0[j] + a];
-      n = w.n;
-      const uint64_t mv = w.maxv;
-      const uint32_t L = w.L, cand = w.cand, nc = w.nchunks;
-      uint64_t hw = 0;
-#pragma unroll
-      for (int q = 0; q < kWordParts; q++) hw += w.huff_words[q];
-      U = w.U;
-      const int wd = bitwidth64(mv);
-      const uint64_t fixed = 4 * ((n * (uint64_t)wd + 31) / 32);
-      const uint64_t huff = 4ull * U + 4ull * nc + 4ull * hw;
-      const bool use_h = cand && huff < fixed;
-      coder = use_h ? 1u : 0u;
-      param = use_h ? L : (uint32_t)wd;
-      if (!use_h) U = 0;
-      nbytes = use_h ? huff : fixed;
-      w.coder = coder;
-      w.w = (uint32_t)wd;
-      w.nbytes = nbytes;
-      s_nb[j][a] = nbytes;
+      ch = choose_coder(w);
+      w.coder = ch.coder;
+      w.w = ch.wd;
+      w.nbytes = ch.nbytes;
+      s_nb[j][a] = ch.nbytes;
     }
     __syncthreads();
     unsigned long long size = 0;
@@ -980,15 +999,7 @@ __device__ void layout_records(ArrWork* W, EncRec* recs, const EncRec& rec0, int
       const uint64_t aoff = s_nb[j][a];
       W[s_a0[j] + a].off = aoff;
       const unsigned long long roff = s_roff[j];
-      if (roff + s_size[j] <= cap) {
-        uint8_t* o = out + roff;
-        const uint64_t d = (uint64_t)kHdrBytes + 8ull * s_F[j] + (uint64_t)kDirBytes * a;
-        put32(o, d, coder | (param << 8));
-        put32(o, d + 4, U);
-        put64(o, d + 8, n);
-        put64(o, d + 16, aoff);
-        put64(o, d + 24, nbytes);
-      }
+      if (roff + s_size[j] <= cap) write_dir(out + roff, s_F[j], a, ch, aoff);
     }
     carry += tot;
     __syncthreads();
@@ -999,15 +1010,22 @@ __device__ void layout_records(ArrWork* W, EncRec* recs, const EncRec& rec0, int
 
 // ------------------------------------------------------------------ packing
 // Workgroup lb of the nb that pack fixed-length array a.
-__device__ inline void pack_fixed_block(const EncArr* E, const ArrWork* W, const EncRec* recs,
-                                        uint32_t a, uint32_t lb, uint32_t nb, uint8_t* out,
-                                        const uint32_t* err) {
+// Where an array goes, as the layout decided: its coder and fixed width, and
+// its first byte in the output (valid when the record fits).
+struct ArrPlace {
+  uint32_t coder, wd;
+  uint8_t* dst;
+  bool fits;
+};
+
+__device__ inline void pack_fixed_block(const EncArr* E, const ArrWork* W, uint32_t a,
+                                        const ArrPlace& pl, uint32_t lb, uint32_t nb) {
+  if (pl.coder != 0 || pl.wd == 0 || !pl.fits) return;
   const ArrWork& w = W[a];
-  if (w.coder != 0 || w.w == 0 || (*err & kErrCapacity)) return;
   const ArrIn in = E[a].in;
-  const uint64_t n = w.n, wd = w.w;
+  const uint64_t n = w.n, wd = pl.wd;
   const uint64_t nwords = (n * wd + 31) / 32;
-  uint32_t* dst = reinterpret_cast<uint32_t*>(out + recs[E[a].rec].off + w.off);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(pl.dst);
   const uint64_t stride = (uint64_t)nb * kThreads;
   for (uint64_t j = (uint64_t)lb * kThreads + threadIdx.x; j < nwords; j += stride) {
     const uint64_t bit0 = 32 * j;
@@ -1471,18 +1489,18 @@ __global__ __launch_bounds__(kHT) void k_layout(ArrWork* W, EncRec* recs, const 
 // 256 chunks at a time, scanning their counts and copying their words as one
 // flat range (a word finds its chunk by binary search over the tile's
 // offsets), so that loads of different chunks overlap.
-__device__ inline void copy_huff_block(const EncArr* E, const ArrWork* W, const EncRec* recs,
-                                       uint32_t a, uint32_t lb, uint32_t nb, const uint32_t* cnt,
-                                       const uint32_t* stage, uint32_t slot32, uint32_t slot64,
-                                       uint8_t* out, const uint32_t* err) {
+__device__ inline void copy_huff_block(const EncArr* E, const ArrWork* W, uint32_t a,
+                                       const ArrPlace& pl, uint32_t lb, uint32_t nb,
+                                       const uint32_t* cnt, const uint32_t* stage,
+                                       uint32_t slot32, uint32_t slot64, const uint32_t* err) {
   __shared__ unsigned long long sm[kThreads / kWave + 1];
   __shared__ uint32_t c_end[kThreads];  // inclusive word ends inside the tile
   const ArrWork& w = W[a];
-  if (w.coder != 1 || (*err & (kErrCapacity | kErrCorrupt))) return;
+  if (pl.coder != 1 || !pl.fits || (*err & kErrCorrupt)) return;
   const EncArr& e = E[a];
   const uint32_t U = w.U, nchunks = w.nchunks;
   const uint32_t slot = e.in.is64 ? slot64 : slot32;
-  uint32_t* dst = reinterpret_cast<uint32_t*>(out + recs[e.rec].off + w.off);
+  uint32_t* dst = reinterpret_cast<uint32_t*>(pl.dst);
   uint32_t* dpay = dst + U + nchunks;
   const uint32_t* cnta = cnt + e.cw0;
   const uint32_t* pay = stage + e.stage0;
@@ -1546,23 +1564,75 @@ __device__ inline void copy_huff_block(const EncArr* E, const ArrWork* W, const 
 
 // The arrays' payloads once the layout has placed them: workgroups below
 // fixed_blocks pack fixed-length arrays, the rest copy Huffman arrays.
-__global__ __launch_bounds__(kThreads) void k_emit(const EncArr* E, const ArrWork* W,
-                                                   const EncRec* recs, const uint32_t* pre_fixed,
+// Fixed-length arrays are packed in place and the Huffman payloads gathered
+// from their staging.  A launch of one record (fold) has no layout kernel:
+// every workgroup decides the record's layout itself from the arrays' sizes
+// (a few loads) and workgroup 0 writes what the layout kernel would have (the
+// header, the directory, the record's offsets, the coder decisions and the
+// capacity error).
+__global__ __launch_bounds__(kThreads) void k_emit(const EncArr* E, ArrWork* W, EncRec* recs,
+                                                   const EncRec rec0, int fold,
+                                                   const uint32_t* pre_fixed,
                                                    uint32_t fixed_blocks, const uint32_t* pre_copy,
                                                    int NA, const uint32_t* cnt,
                                                    const uint32_t* stage, uint32_t slot32,
-                                                   uint32_t slot64, uint8_t* out,
-                                                   const uint32_t* err) {
-  if (blockIdx.x < fixed_blocks) {
-    const uint32_t a = array_of_block_few(pre_fixed, NA, blockIdx.x);
-    pack_fixed_block(E, W, recs, a, blockIdx.x - pre_fixed[a], pre_fixed[a + 1] - pre_fixed[a],
-                     out, err);
+                                                   uint32_t slot64, uint8_t* out, uint64_t cap,
+                                                   unsigned long long* offs,
+                                                   const unsigned long long* base_dev,
+                                                   uint32_t* err) {
+  const bool fixed = blockIdx.x < fixed_blocks;
+  const uint32_t b = fixed ? blockIdx.x : blockIdx.x - fixed_blocks;
+  const uint32_t* pre = fixed ? pre_fixed : pre_copy;
+  const uint32_t a = array_of_block_few(pre, NA, b);
+  const uint32_t lb = b - pre[a], nb = pre[a + 1] - pre[a];
+  ArrPlace pl;
+  if (fold) {
+    __shared__ ArrChoice s_ch[kMaxArrays];
+    __shared__ unsigned long long s_aoff[kMaxArrays + 1], s_roff;
+    const int t = threadIdx.x, A = rec0.h.A, F = rec0.h.F;
+    const unsigned long long carry = base_dev ? *base_dev : 0ull;
+    if (t < A) s_ch[t] = choose_coder(W[rec0.a0 + t]);
+    __syncthreads();
+    if (t == 0) {
+      uint64_t off = (uint64_t)kHdrBytes + 8ull * F + (uint64_t)kDirBytes * A;
+      for (int q = 0; q < A; q++) {
+        s_aoff[q] = off;
+        off += s_ch[q].nbytes;
+      }
+      s_aoff[A] = off;  // the record's size
+      s_roff = carry;
+    }
+    __syncthreads();
+    const uint64_t size = s_aoff[A], roff = s_roff;
+    const bool fits = roff + size <= cap;
+    if (blockIdx.x == 0) {
+      if (t < A) {
+        ArrWork& w = W[rec0.a0 + t];
+        w.coder = s_ch[t].coder;
+        w.w = s_ch[t].wd;
+        w.nbytes = s_ch[t].nbytes;
+        w.off = s_aoff[t];
+        if (fits) write_dir(out + roff, F, t, s_ch[t], s_aoff[t]);
+      }
+      if (t == 0) {
+        recs[0].size = size;
+        recs[0].off = roff;
+        offs[0] = roff;
+        offs[1] = roff + size;
+        if (fits) write_header(rec0.h, rec0.h.mode == 0 ? *rec0.B_dev : 0ull, size, out + roff);
+        else atomicOr(err, kErrCapacity);
+      }
+    }
+    const uint32_t q = a - rec0.a0;
+    pl = ArrPlace{s_ch[q].coder, s_ch[q].wd, out + roff + s_aoff[q], fits};
   } else {
-    const uint32_t b = blockIdx.x - fixed_blocks;
-    const uint32_t a = array_of_block_few(pre_copy, NA, b);
-    copy_huff_block(E, W, recs, a, b - pre_copy[a], pre_copy[a + 1] - pre_copy[a], cnt, stage,
-                    slot32, slot64, out, err);
+    const ArrWork& w = W[a];
+    pl = ArrPlace{w.coder, w.w, out + recs[E[a].rec].off + w.off, !(*err & kErrCapacity)};
   }
+  if (fixed)
+    pack_fixed_block(E, W, a, pl, lb, nb);
+  else
+    copy_huff_block(E, W, a, pl, lb, nb, cnt, stage, slot32, slot64, err);
 }
 
 // ------------------------------------------------------------------ decode
@@ -2099,10 +2169,15 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
     launch_timed("pack_huff", L.values * 6ull, kernel, g, kThreads, shm, s, L.arrs, work,
                  pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, slot64, err);
   }
-  launch_timed("layout", 0, k_layout, 1, kHT, 0, s, work, L.recs, L.rec0, L.R, out, cap, offs,
-               base, err);
-  launch_timed("emit", L.values * 6ull, k_emit, L.fixed_blocks + L.copy_blocks, kThreads, 0, s,
-               L.arrs, work, L.recs, pre_fixed, L.fixed_blocks, pre_copy, NA, X.chunk_words, X.stage, slot32, slot64, out, err);
+  const uint32_t emit_blocks = L.fixed_blocks + L.copy_blocks;
+  const int fold = L.R == 1 && emit_blocks > 0;  // the emit workgroups lay the record out
+  if (!fold)
+    launch_timed("layout", 0, k_layout, 1, kHT, 0, s, work, L.recs, L.rec0, L.R, out, cap, offs,
+                 base, err);
+  if (emit_blocks)
+    launch_timed("emit", L.values * 6ull, k_emit, emit_blocks, kThreads, 0, s, L.arrs, work,
+                 L.recs, L.rec0, fold, pre_fixed, L.fixed_blocks, pre_copy, NA, X.chunk_words,
+                 X.stage, slot32, slot64, out, cap, offs, base, err);
 }
 
 uint32_t decode_blocks(const DecArr& d, int chunk_log2, bool huff) {
