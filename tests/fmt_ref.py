@@ -98,8 +98,9 @@ def unzigzag(z: int) -> int:
     return -(z >> 1) - 1 if z & 1 else z >> 1
 
 
-def parse(rec: bytes) -> dict:
-    """Header, grids, directory and the decoded symbol arrays of one record."""
+def parse(rec: bytes, arrays: bool = True) -> dict:
+    """Header, grids, directory and (unless arrays is False) the decoded symbol
+    arrays of one record."""
     assert rec[:4] == MAGIC
     version, mode, F, k, cl, A, flags, hdr = struct.unpack_from("<HBBBBBBI", rec, 4)
     n, B, total = struct.unpack_from("<QQQ", rec, 16)
@@ -108,12 +109,13 @@ def parse(rec: bytes) -> dict:
     assert version == 1 and total == len(rec) and hdr == 80 + 8 * F + 32 * A
     assert A == (F + 2 if mode == 0 else F)
     grids = [struct.unpack_from("<ff", rec, 80 + 8 * f) for f in range(F)]
-    arrays, dirs, off = [], [], hdr
+    want_arrays, arrays, dirs, off = arrays, [], [], hdr
     for a in range(A):
         coder, param, _r, used, an, aoff, anb = struct.unpack_from("<BBHIQQQ", rec, 80 + 8 * F + 32 * a)
         assert aoff == off
         dirs.append(dict(coder=coder, param=param, used=used, n=an, off=aoff, nbytes=anb))
-        arrays.append(decode_array(rec[aoff:aoff + anb], an, coder, param, used, cl))
+        if want_arrays:
+            arrays.append(decode_array(rec[aoff:aoff + anb], an, coder, param, used, cl))
         off += anb
     assert off == total
     return dict(mode=mode, F=F, k=k, chunk_log2=cl, n=n, B=B, bn=bn, seq=seq, ref_seq=ref_seq,

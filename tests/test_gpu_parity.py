@@ -259,3 +259,83 @@ def test_temporal_residuals_above_a_byte_fixed_length(lcp):
         assert rec == want, f"frame {t}: " + diff_report(rec, want)
     P = fmt_ref.parse(want)
     assert P["mode"] == 1 and all(d["coder"] == 0 and d["param"] >= 9 for d in P["dirs"])
+
+
+def temporal_pair(lcp, n, cl, resid, seed, arrays=True):
+    """Frame 0 spatial, frame 1 forced temporal with the given residuals per
+    field; both records and the decoded frame 1 against the oracle."""
+    x0 = datagen.uniform_frame(n, hi=50.0, seed=seed)
+    grids = O.grids_for(x0, O.EB_ABS, 1e-3)
+    x1 = np.empty_like(x0)
+    for f in range(3):
+        x1[f] = O.reconstruct(O.quantize(x0[f], grids[f]) + resid[f], grids[f])
+    ost = O.Stream(O.EB_ABS, 1e-3, batch_size=0, block_log2=6, chunk_log2=cl, max_n=n)
+    plan = lcp.Plan(1e-3, lcp.EB_ABS, multi_frame=True, batch_size=0, block_log2=6, chunk_log2=cl,
+                    max_particles=n)
+    recs = []
+    for t, (x, m) in enumerate([(x0, O.METHOD_S), (x1, O.METHOD_T)]):
+        want, wused, _ = ost.compress(x, method=m)
+        out, offs, used, _ = plan.compress([torch.from_numpy(x).cuda()], methods=[m])
+        rec = out[offs[0]:offs[1]].cpu().numpy().tobytes()
+        assert used[0] == wused == m, t
+        assert rec == want, f"frame {t}: " + diff_report(rec, want)
+        recs.append(want)
+    dplan = lcp.Plan(1e-3, lcp.EB_ABS, multi_frame=True, batch_size=0, block_log2=6,
+                     chunk_log2=cl, max_particles=n)
+    buf = np.frombuffer(b"".join(recs), np.uint8)
+    offs = [0, len(recs[0]), len(recs[0]) + len(recs[1])]
+    dec = dplan.decompress(torch.from_numpy(buf.copy()).cuda(), offs)
+    dst = O.Stream(O.EB_ABS, 1e-3, batch_size=0, block_log2=6, chunk_log2=cl, max_n=n)
+    for t in range(2):
+        w = dst.decompress(recs[t])
+        assert all(bits_equal(dec[t][f].cpu().numpy(), w[f]) for f in range(3)), t
+    return fmt_ref.parse(recs[1], arrays)
+
+
+@pytest.mark.parametrize("cl", [5, 6, 7, 8, 9, 10, 11, 12])
+def test_temporal_chunk_sizes_ragged(lcp, cl):
+    """Small residuals (the byte path; nine in ten zero, so that Huffman wins
+    even with 32-value chunks) at every chunk size, with a ragged last chunk and
+    a length that is not a multiple of 16, so that the second and third
+    fields' bytes start unaligned."""
+    n = 40 * (1 << cl) + 37
+    rng = np.random.default_rng(100 + cl)
+    resid = [np.where(rng.random(n) < 0.9, 0, rng.integers(-3, 4, size=n)) for _ in range(3)]
+    print(f"case cl={cl} n={n}", flush=True)
+    P = temporal_pair(lcp, n, cl, resid, seed=200 + cl)
+    # with 32-value chunks the chunk index alone costs a bit per value: fixed wins
+    assert P["mode"] == 1 and all(d["coder"] == (1 if cl >= 6 else 0) for d in P["dirs"])
+
+
+@pytest.mark.parametrize("cl", [6, 8, 10])
+def test_temporal_escapes_and_many_rounds(lcp, cl):
+    """Mostly small residuals with one in a thousand far out (zigzag values
+    past a byte, some past the direct symbols, so raw extra bits follow their
+    codes), over enough chunks that each packing wave takes several rounds."""
+    n = (4100 << cl) // 4 * 4 + 11 if cl < 10 else (1 << 20) + 11
+    rng = np.random.default_rng(300 + cl)
+    resid = []
+    for f in range(3):
+        r = rng.integers(-2, 3, size=n)
+        far = rng.random(n) < 1e-3
+        r[far] = rng.integers(-6000, 6000, size=int(far.sum()))
+        resid.append(r)
+    assert min(int(np.abs(r).max()) for r in resid) >= 2048  # zigzag values past 4096
+    print(f"case cl={cl} n={n}", flush=True)
+    P = temporal_pair(lcp, n, cl, resid, seed=400 + cl, arrays=False)
+    assert all(d["coder"] == 1 for d in P["dirs"])
+
+
+def test_temporal_sixty_symbols(lcp):
+    """Residuals spread over [-31, 31] (each value at least once, the rest
+    Gaussian with sigma 8): 63 symbols, all below 64, for the one-wave code
+    builder with nearly every lane in use."""
+    n = 50000
+    rng = np.random.default_rng(501)
+    resid = []
+    for _ in range(3):
+        r = np.clip(np.rint(rng.normal(0.0, 8.0, size=n)), -31, 31).astype(np.int64)
+        r[:63] = np.arange(-31, 32)
+        resid.append(r)
+    P = temporal_pair(lcp, n, 10, resid, seed=502)
+    assert all(d["coder"] == 1 and d["used"] == 63 for d in P["dirs"])
