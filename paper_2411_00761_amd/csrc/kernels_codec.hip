@@ -1900,6 +1900,10 @@ __device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const 
   const bool vec = MODE >= 2 && (reinterpret_cast<uintptr_t>(d.out) & 15) == 0;
   typedef __attribute__((address_space(1))) uint8_t* GOut8;
   const uint32_t lim = d.limit > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)d.limit;
+  static_assert(2 * kMaxLen <= 32, "two codes fit the bits one top-up guarantees");
+  const int P = L <= 4 ? 8 : L <= 8 ? 4 : 2;  // symbols per top-up of the bit buffer
+  const uint32_t pmask = (uint32_t)P - 1u;
+  const int group_bits = P * L;
   for (uint64_t i0 = cbeg; i0 < cend; i0 += kRound) {
     if (pfpos == r.wpos && r.wpos < r.cw && r.wpos + K <= r.rpos + kRing) {
 #pragma unroll
@@ -1926,6 +1930,10 @@ __device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const 
       // entry, code longer than the bits left, value over the limit, a short
       // round) marks the lane, which then starts the round again on the
       // careful path.
+      // The buffer is topped up once per group of P symbols: after a top-up it
+      // holds at least 33 bits (unless the chunk's words ran out), and P codes
+      // of at most L bits fit in 32, so within a group no symbol needs a
+      // refill or a length check (P = 8, 4, 2 for L up to 4, 8, 13).
       const uint64_t buf0 = r.buf;
       const int nb0 = r.nb;
       const uint32_t rpos0 = r.rpos, wpos0 = r.wpos;
@@ -1933,18 +1941,21 @@ __device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const 
       if (!redo) {
 #pragma unroll
         for (int j = 0; j < kRound; j++) {
-          const bool need = r.nb <= 32 && r.rpos < r.cw;
-          const bool have = r.rpos < r.wpos;
-          const bool app = need && have;
-          const uint32_t w = r.ring[(r.rpos & (kRing - 1)) * kThreads];
-          const int sh = app ? 32 - r.nb : 0;
-          r.buf |= app ? ((uint64_t)w << sh) : 0ull;
-          r.nb += app ? 32 : 0;
-          r.rpos += app ? 1u : 0u;
+          if ((j & pmask) == 0) {
+            const bool need = r.nb <= 32 && r.rpos < r.cw;
+            const bool have = r.rpos < r.wpos;
+            const bool app = need && have;
+            const uint32_t w = r.ring[(r.rpos & (kRing - 1)) * kThreads];
+            const int sh = app ? 32 - r.nb : 0;
+            r.buf |= app ? ((uint64_t)w << sh) : 0ull;
+            r.nb += app ? 32 : 0;
+            r.rpos += app ? 1u : 0u;
+            redo |= (need && !have) || r.nb < group_bits;
+          }
           const uint32_t e16 = lut[(uint32_t)(r.buf >> (64 - L))];
           const int l = (int)(e16 >> 12);
           const uint32_t sym = e16 & 0xFFFu;
-          redo |= (need && !have) || e16 == 0 || l > r.nb || sym >= lim;
+          redo |= e16 == 0 || sym >= lim;
           r.buf <<= l;
           r.nb -= l;
           vals[j] = (uint32_t)out_value<MODE>(sym);
