@@ -1777,6 +1777,11 @@ __device__ inline bool store_value(const DecArr& d, uint64_t i, uint64_t v) {
 // every table lookup would wait for them.
 constexpr int kRound = 16;
 constexpr int kRing = 16;
+// Per wave: the staged payload of its 64 chunks (or the lanes' rings).
+constexpr int kStageWords = 3072;  // 48 words (1536 bits) per chunk on average
+constexpr int kStageBatch = 8;  // words per lane loaded together while staging
+static_assert(kStageWords >= kRing * kWave, "a wave's area holds its lanes' rings");
+static_assert(kThreads / kWave * kStageWords * 4 + (2 << kMaxLen) <= 65536, "decoder LDS");
 typedef const __attribute__((address_space(1))) uint32_t* GWords;
 typedef __attribute__((address_space(1))) uint64_t* GOut64;
 typedef __attribute__((address_space(1))) uint32_t* GOut32;
@@ -1789,12 +1794,12 @@ struct RingReader {
   int nb;
   uint32_t rpos, wpos, cw;
   GWords pay;          // the chunk's first word
-  uint32_t* ring;      // slot s of this thread at ring[s * kThreads]
+  uint32_t* ring;      // slot s of this thread at ring[s * kWave] (the wave's own area)
   __device__ inline void refill() {
     if (nb <= 32 && rpos < cw) {
       uint32_t w;
       if (rpos < wpos) {
-        w = ring[(rpos & (kRing - 1)) * kThreads];
+        w = ring[(rpos & (kRing - 1)) * kWave];
       } else {
         w = pay[rpos];
         wpos = rpos + 1;
@@ -1806,8 +1811,24 @@ struct RingReader {
   }
 };
 
+// A chunk whose payload words all sit in LDS (staged by its wave).
+struct StageReader {
+  uint64_t buf;
+  int nb;
+  uint32_t rpos, cw;
+  const uint32_t* w;  // the chunk's first word in LDS
+  __device__ inline void refill() {
+    if (nb <= 32 && rpos < cw) {
+      buf |= (uint64_t)w[rpos] << (32 - nb);
+      nb += 32;
+      rpos++;
+    }
+  }
+};
+
 // Raw bits that follow a length-class symbol (rare): up to 63 bits.
-__device__ inline bool read_extra(RingReader& r, int eb, uint64_t* x) {
+template <typename Reader>
+__device__ inline bool read_extra(Reader& r, int eb, uint64_t* x) {
   uint64_t v = 0;
   int rem = eb;
   while (rem > 0) {
@@ -1825,7 +1846,8 @@ __device__ inline bool read_extra(RingReader& r, int eb, uint64_t* x) {
 
 // One symbol; false on a malformed stream.  A refill leaves at least 33 bits
 // unless the chunk ends, so one test covers the code itself (at most 13 bits).
-__device__ inline bool decode_symbol(RingReader& r, const uint16_t* lut, const uint32_t* glut,
+template <typename Reader>
+__device__ inline bool decode_symbol(Reader& r, const uint16_t* lut, const uint32_t* glut,
                                      int L, const DecArr& d, uint64_t* out) {
   if (r.nb <= 32) r.refill();
   const uint32_t win = (uint32_t)(r.buf >> (64 - L));
@@ -1862,6 +1884,40 @@ __device__ inline uint32_t byte_of(uint32_t r, const DecArr& d, uint64_t i) {
   return 0x80u;
 }
 
+// A round's values (cnt of them from index i0) to the output array of mode
+// 2..4; vec: the output is 16-byte aligned.
+template <int MODE>
+__device__ inline void store_round(const DecArr& d, const uint32_t* vals, int cnt, uint64_t i0,
+                                   bool vec) {
+  typedef __attribute__((address_space(1))) uint8_t* GOut8;
+  if (MODE == 4) {
+    // bytes: four values to a word, one 16-byte store per round
+    uint32_t b[kRound];
+#pragma unroll
+    for (int j = 0; j < kRound; j++) b[j] = j < cnt ? byte_of(vals[j], d, i0 + j) : 0u;
+    if (vec && cnt == kRound) {
+      uint32_t wd[kRound / 4];
+#pragma unroll
+      for (int q = 0; q < kRound / 4; q++)
+        wd[q] = b[4 * q] | (b[4 * q + 1] << 8) | (b[4 * q + 2] << 16) | (b[4 * q + 3] << 24);
+      *(GOut128)((GOut8)d.out + i0) = U32x4{wd[0], wd[1], wd[2], wd[3]};
+    } else {
+#pragma unroll
+      for (int j = 0; j < kRound; j++)
+        if (j < cnt) ((GOut8)d.out)[i0 + j] = (uint8_t)b[j];
+    }
+  } else if (vec && cnt == kRound) {
+    GOut128 o = (GOut128)((GOut32)d.out + i0);
+#pragma unroll
+    for (int q = 0; q < kRound / 4; q++)
+      o[q] = U32x4{vals[4 * q], vals[4 * q + 1], vals[4 * q + 2], vals[4 * q + 3]};
+  } else {
+#pragma unroll
+    for (int j = 0; j < kRound; j++)
+      if (j < cnt) ((GOut32)d.out)[i0 + j] = vals[j];
+  }
+}
+
 template <int MODE, int K>
 __device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const uint32_t* glut,
                                     int L, uint64_t c, int chunk_log2, uint32_t* ring,
@@ -1879,7 +1935,7 @@ __device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const 
   RingReader r;
   r.pay = offs + nchunks + wbeg;
   r.cw = (uint32_t)(wend - wbeg);
-  r.ring = ring + threadIdx.x;
+  r.ring = ring + lane_id();
   r.buf = 0;
   r.nb = 0;
   r.rpos = 0;
@@ -1889,7 +1945,7 @@ __device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const 
 #pragma unroll
     for (int j = 0; j < kRing; j++) w0[j] = r.pay[min((uint64_t)j, last)];
 #pragma unroll
-    for (int j = 0; j < kRing; j++) r.ring[j * kThreads] = w0[j];
+    for (int j = 0; j < kRing; j++) r.ring[j * kWave] = w0[j];
   }
   r.wpos = min((uint32_t)kRing, r.cw);
   uint32_t pf[K];
@@ -1907,7 +1963,7 @@ __device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const 
   for (uint64_t i0 = cbeg; i0 < cend; i0 += kRound) {
     if (pfpos == r.wpos && r.wpos < r.cw && r.wpos + K <= r.rpos + kRing) {
 #pragma unroll
-      for (int j = 0; j < K; j++) r.ring[((r.wpos + j) & (kRing - 1)) * kThreads] = pf[j];
+      for (int j = 0; j < K; j++) r.ring[((r.wpos + j) & (kRing - 1)) * kWave] = pf[j];
       r.wpos = min(r.wpos + K, r.cw);
     }
     pfpos = r.wpos;
@@ -1945,7 +2001,7 @@ __device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const 
             const bool need = r.nb <= 32 && r.rpos < r.cw;
             const bool have = r.rpos < r.wpos;
             const bool app = need && have;
-            const uint32_t w = r.ring[(r.rpos & (kRing - 1)) * kThreads];
+            const uint32_t w = r.ring[(r.rpos & (kRing - 1)) * kWave];
             const int sh = app ? 32 - r.nb : 0;
             r.buf |= app ? ((uint64_t)w << sh) : 0ull;
             r.nb += app ? 32 : 0;
@@ -1979,33 +2035,73 @@ __device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const 
           }
         }
       }
-      if (MODE == 4) {
-        // bytes: four values to a word, one 16-byte store per round
-        uint32_t b[kRound];
+      store_round<MODE>(d, vals, cnt, i0, vec);
+    }
+  }
+}
+
+// A chunk of an array of mode 2..4 whose cw payload words the wave has staged
+// in LDS at w: the same rounds as decode_chunk (a branch-free full round, the
+// careful path for anything unusual), with no loads from global memory.
+template <int MODE>
+__device__ inline void decode_chunk_staged(const DecArr& d, const uint16_t* lut,
+                                           const uint32_t* glut, int L, uint64_t c,
+                                           int chunk_log2, const uint32_t* w, uint32_t cw,
+                                           uint32_t* err) {
+  const uint64_t C = 1ull << chunk_log2;
+  StageReader r{0ull, 0, 0u, cw, w};
+  const uint64_t cbeg = c * C, cend = min(d.n, cbeg + C);
+  const bool vec = (reinterpret_cast<uintptr_t>(d.out) & 15) == 0;
+  const uint32_t lim = d.limit > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)d.limit;
+  const int P = L <= 4 ? 8 : L <= 8 ? 4 : 2;  // symbols per top-up of the bit buffer
+  const uint32_t pmask = (uint32_t)P - 1u;
+  const int group_bits = P * L;
+  for (uint64_t i0 = cbeg; i0 < cend; i0 += kRound) {
+    const int cnt = (int)min((uint64_t)kRound, cend - i0);
+    uint32_t vals[kRound];
+    const uint64_t buf0 = r.buf;
+    const int nb0 = r.nb;
+    const uint32_t rpos0 = r.rpos;
+    bool redo = cnt < kRound;
+    if (!redo) {
 #pragma unroll
-        for (int j = 0; j < kRound; j++) b[j] = j < cnt ? byte_of(vals[j], d, i0 + j) : 0u;
-        if (vec && cnt == kRound) {
-          uint32_t wd[kRound / 4];
-#pragma unroll
-          for (int q = 0; q < kRound / 4; q++)
-            wd[q] = b[4 * q] | (b[4 * q + 1] << 8) | (b[4 * q + 2] << 16) | (b[4 * q + 3] << 24);
-          *(GOut128)((GOut8)d.out + i0) = U32x4{wd[0], wd[1], wd[2], wd[3]};
-        } else {
-#pragma unroll
-          for (int j = 0; j < kRound; j++)
-            if (j < cnt) ((GOut8)d.out)[i0 + j] = (uint8_t)b[j];
+      for (int j = 0; j < kRound; j++) {
+        if ((j & pmask) == 0) {
+          const bool app = r.nb <= 32 && r.rpos < r.cw;
+          const uint32_t wd = w[min(r.rpos, r.cw - 1u)];
+          const int sh = app ? 32 - r.nb : 0;
+          r.buf |= app ? ((uint64_t)wd << sh) : 0ull;
+          r.nb += app ? 32 : 0;
+          r.rpos += app ? 1u : 0u;
+          redo |= r.nb < group_bits;
         }
-      } else if (vec && cnt == kRound) {
-        GOut128 o = (GOut128)((GOut32)d.out + i0);
-#pragma unroll
-        for (int q = 0; q < kRound / 4; q++)
-          o[q] = U32x4{vals[4 * q], vals[4 * q + 1], vals[4 * q + 2], vals[4 * q + 3]};
-      } else {
-#pragma unroll
-        for (int j = 0; j < kRound; j++)
-          if (j < cnt) ((GOut32)d.out)[i0 + j] = vals[j];
+        const uint32_t e16 = lut[(uint32_t)(r.buf >> (64 - L))];
+        const int l = (int)(e16 >> 12);
+        const uint32_t sym = e16 & 0xFFFu;
+        redo |= e16 == 0 || sym >= lim;
+        r.buf <<= l;
+        r.nb -= l;
+        vals[j] = (uint32_t)out_value<MODE>(sym);
       }
     }
+    if (redo) {
+      r.buf = buf0;
+      r.nb = nb0;
+      r.rpos = rpos0;
+#pragma unroll
+      for (int j = 0; j < kRound; j++) {
+        vals[j] = 0;
+        if (j < cnt) {
+          uint64_t v;
+          if (!decode_symbol(r, lut, glut, L, d, &v)) {
+            atomicOr(err, kErrCorrupt);
+            return;
+          }
+          vals[j] = (uint32_t)out_value<MODE>(v);
+        }
+      }
+    }
+    store_round<MODE>(d, vals, cnt, i0, vec);
   }
 }
 
@@ -2029,16 +2125,16 @@ __device__ inline void decode_chunk_k(int K, const DecArr& d, const uint16_t* lu
   }
 }
 
-// Dynamic LDS: the rings (kRing x kThreads words), then the 16-bit table of
-// 2^lut_log2 entries (lut_log2: the longest code among the launch's arrays).
+// Dynamic LDS: an area of kStageWords words per wave (its chunks' staged
+// payload, or its lanes' rings), then the 16-bit table of 2^lut_log2 entries
+// (lut_log2: the longest code among the launch's arrays); 64 KB at most.
 __global__ __launch_bounds__(kThreads) void k_decode_huff(const DecArr* arrs,
                                                           const uint32_t* prefix, int A,
                                                           int chunk_log2,
                                                           const uint32_t* lut_all, int lut_log2,
                                                           uint32_t* err) {
   extern __shared__ uint32_t dyn[];
-  uint32_t* ring = dyn;
-  uint16_t* lut = reinterpret_cast<uint16_t*>(dyn + kThreads * kRing);
+  uint16_t* lut = reinterpret_cast<uint16_t*>(dyn + kThreads / kWave * kStageWords);
   const uint32_t a = array_of_block(prefix, A, blockIdx.x);
   const DecArr d = arrs[a];
   if (d.coder != 1 || d.param < 1 || d.param > kMaxLen || (*err & kErrCorrupt)) return;
@@ -2059,15 +2155,64 @@ __global__ __launch_bounds__(kThreads) void k_decode_huff(const DecArr* arrs,
     lut[i] = (uint16_t)(sym < (uint32_t)kDirect && l ? (l << 12) | sym : 0u);
   }
   __syncthreads();
+  // The wave's chunks are consecutive, so their payloads are one range of
+  // words: when it fits the wave's area it is copied there with coalesced
+  // loads (one request per 64 words, where a lane reading its own chunk would
+  // touch a line per lane per word) and every lane decodes from LDS; else the
+  // lanes read through their rings.
   const uint64_t c = (uint64_t)(blockIdx.x - prefix[a]) * kThreads + threadIdx.x;
-  if (c >= nchunks) return;
+  const bool valid = c < nchunks;
+  const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane(wave_id());
+  uint32_t* area = dyn + (uint64_t)wv * kStageWords;
+  const uint64_t vmask = __ballot(valid);
+  if (vmask == 0) return;
+  const GWords offs = (GWords)d.data + d.used;
+  const uint64_t payload_words = d.nbytes / 4 - d.used - nchunks;
+  const uint64_t wbeg = valid ? (c ? offs[c - 1] : 0) : 0, wend = valid ? offs[c] : 0;
+  // a chunk holds at least one symbol, so at least one word
+  const bool bad = valid && (wbeg >= wend || wend > payload_words ||
+                             (c == nchunks - 1 && wend != payload_words));
+  const uint32_t last_lane = 63u - (uint32_t)__builtin_clzll(vmask);
+  const uint64_t r0 = (uint64_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)wbeg) |
+                      ((uint64_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(wbeg >> 32)) << 32);
+  const uint64_t r1 = (uint64_t)__builtin_amdgcn_readlane((int)(uint32_t)wend, last_lane) |
+                      ((uint64_t)__builtin_amdgcn_readlane((int)(uint32_t)(wend >> 32), last_lane) << 32);
   const int K = ring_words(d, nchunks);
+  if ((d.mode >= 2) && __ballot(bad) == 0 && r1 > r0 && r1 - r0 <= (uint64_t)kStageWords) {
+    const uint32_t S = (uint32_t)(r1 - r0);
+    const GWords src_w = offs + nchunks + r0;
+    const uint32_t lane = (uint32_t)lane_id();
+    for (uint32_t j0 = 0; j0 < S; j0 += kWave * kStageBatch) {
+      uint32_t v[kStageBatch];
+#pragma unroll
+      for (int q = 0; q < kStageBatch; q++) {
+        const uint32_t j = j0 + q * kWave + lane;
+        v[q] = j < S ? src_w[j] : 0u;
+      }
+#pragma unroll
+      for (int q = 0; q < kStageBatch; q++) {
+        const uint32_t j = j0 + q * kWave + lane;
+        if (j < S) area[j] = v[q];
+      }
+    }
+    wave_lds_sync();
+    if (!valid) return;
+    const uint32_t* wch = area + (uint32_t)(wbeg - r0);
+    const uint32_t cw = (uint32_t)(wend - wbeg);
+    switch (d.mode) {
+      case 2: decode_chunk_staged<2>(d, lut, src, L, c, chunk_log2, wch, cw, err); break;
+      case 3: decode_chunk_staged<3>(d, lut, src, L, c, chunk_log2, wch, cw, err); break;
+      default: decode_chunk_staged<4>(d, lut, src, L, c, chunk_log2, wch, cw, err); break;
+    }
+    return;
+  }
+  if (!valid) return;
   switch (d.mode) {
-    case 0: decode_chunk_k<0>(K, d, lut, src, L, c, chunk_log2, ring, err); break;
-    case 1: decode_chunk_k<1>(K, d, lut, src, L, c, chunk_log2, ring, err); break;
-    case 2: decode_chunk_k<2>(K, d, lut, src, L, c, chunk_log2, ring, err); break;
-    case 3: decode_chunk_k<3>(K, d, lut, src, L, c, chunk_log2, ring, err); break;
-    default: decode_chunk_k<4>(K, d, lut, src, L, c, chunk_log2, ring, err); break;
+    case 0: decode_chunk_k<0>(K, d, lut, src, L, c, chunk_log2, area, err); break;
+    case 1: decode_chunk_k<1>(K, d, lut, src, L, c, chunk_log2, area, err); break;
+    case 2: decode_chunk_k<2>(K, d, lut, src, L, c, chunk_log2, area, err); break;
+    case 3: decode_chunk_k<3>(K, d, lut, src, L, c, chunk_log2, area, err); break;
+    default: decode_chunk_k<4>(K, d, lut, src, L, c, chunk_log2, area, err); break;
   }
 }
 
@@ -2209,7 +2354,7 @@ void launch_decode(const DecArr* arrs_dev, int A, const uint32_t* huff_prefix_de
   k_lut<<<A, kHT, 0, s>>>(arrs_dev, lut, err);
   if (lut_log2 < 1) lut_log2 = 1;
   if (lut_log2 > kMaxLen) lut_log2 = kMaxLen;
-  const size_t shm = (size_t)kThreads * kRing * 4 + (((size_t)2 << lut_log2) + 3) / 4 * 4;
+  const size_t shm = (size_t)kThreads / kWave * kStageWords * 4 + (((size_t)2 << lut_log2) + 3) / 4 * 4;
   if (huff_blocks)
     launch_timed("decode_huff", bytes, k_decode_huff, huff_blocks, kThreads, shm, s,
                arrs_dev, huff_prefix_dev, A, chunk_log2, lut, lut_log2, err);
