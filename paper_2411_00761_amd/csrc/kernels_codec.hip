@@ -19,6 +19,15 @@ constexpr int kThreads = 256;
 constexpr int kHT = 1024;  // Huffman-build workgroup
 typedef uint32_t U32x4 __attribute__((ext_vector_type(4)));
 
+// Byte arrays (temporal residuals, mode 4) with codes of at most kMW bits
+// also get a table of kMW-bit windows: the bytes of up to six leading codes
+// whose values are small (residuals -8..7) and the bits they take.  It sits
+// in the array's slot of the lookup tables, after the 2^kMaxLen-entry area's
+// first kMOff words (the 32-bit table of such an array has at most 2^kMW).
+constexpr int kMW = 10;
+constexpr uint32_t kMOff = 4096;
+static_assert((1u << kMW) <= kMOff && kMOff + 2 * (1u << kMW) <= (1u << kMaxLen), "window table fits");
+
 __device__ inline uint64_t arr_len(const ArrIn& a) {
   return a.n_dev ? min((uint64_t)*a.n_dev, a.n) : a.n;
 }
@@ -1742,6 +1751,28 @@ __global__ __launch_bounds__(kHT) void k_lut(const DecArr* arrs, uint32_t* lut_a
     const uint32_t l = e >> 16;
     lut[i] = (cstart[lo] <= i && i - cstart[lo] < (1u << (L - l))) ? e : 0u;
   }
+  if (d.mode != 4 || L > kMW) return;
+  __syncthreads();  // the table above is read back
+  // window x: codes taken one after another while the next L bits (zero
+  // padded past the window) name a code that ends inside it and a value
+  // below 16 (and the limit); their residuals as bytes, count and bits
+  uint64_t* win = reinterpret_cast<uint64_t*>(lut + kMOff);
+  const uint32_t lim = d.limit > 0xFFFFFFFFull ? 0xFFFFFFFFu : (uint32_t)d.limit;
+  for (uint32_t x = t; x < (1u << kMW); x += kHT) {
+    uint64_t bytes = 0;
+    uint32_t n = 0, pos = 0;
+    while (n < 6 && pos < (uint32_t)kMW) {
+      const uint32_t idx = pos + L <= (uint32_t)kMW ? (x >> (kMW - pos - L)) & ((1u << L) - 1u)
+                                                    : (x << (pos + L - kMW)) & ((1u << L) - 1u);
+      const uint32_t e = lut[idx], l = e >> 16, sym = e & 0xFFFFu;
+      if (e == 0 || l > (uint32_t)kMW - pos || sym >= 16u || sym >= lim) break;
+      const int32_t r = (int32_t)unzigzag64(sym);
+      bytes |= (uint64_t)(uint8_t)(int8_t)r << (8 * n);
+      n++;
+      pos += l;
+    }
+    win[x] = bytes | ((uint64_t)n << 48) | ((uint64_t)pos << 52);
+  }
 }
 
 __device__ inline bool store_value(const DecArr& d, uint64_t i, uint64_t v) {
@@ -1782,6 +1813,9 @@ constexpr int kStageWords = 3072;  // 48 words (1536 bits) per chunk on average
 constexpr int kStageBatch = 8;  // words per lane loaded together while staging
 static_assert(kStageWords >= kRing * kWave, "a wave's area holds its lanes' rings");
 static_assert(kThreads / kWave * kStageWords * 4 + (2 << kMaxLen) <= 65536, "decoder LDS");
+constexpr int kWinLog2Max = 12;  // longest code of a launch that leaves room for windows
+static_assert(kThreads / kWave * kStageWords * 4 + (2 << kWinLog2Max) + (8 << kMW) <= 65536,
+              "decoder LDS with the window table");
 typedef const __attribute__((address_space(1))) uint32_t* GWords;
 typedef __attribute__((address_space(1))) uint64_t* GOut64;
 typedef __attribute__((address_space(1))) uint32_t* GOut32;
@@ -1851,7 +1885,7 @@ __device__ inline bool decode_symbol(Reader& r, const uint16_t* lut, const uint3
                                      int L, const DecArr& d, uint64_t* out) {
   if (r.nb <= 32) r.refill();
   const uint32_t win = (uint32_t)(r.buf >> (64 - L));
-  const uint32_t e16 = lut[win];
+  const uint32_t e16 = lut ? lut[win] : 0u;
   uint32_t e = ((e16 >> 12) << 16) | (e16 & 0xFFFu);
   if (e16 == 0) e = glut[win];
   const int l = (int)(e >> 16);
@@ -1993,7 +2027,7 @@ __device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const 
       const uint64_t buf0 = r.buf;
       const int nb0 = r.nb;
       const uint32_t rpos0 = r.rpos, wpos0 = r.wpos;
-      bool redo = cnt < kRound;
+      bool redo = cnt < kRound || lut == nullptr;  // no 16-bit table: the careful path only
       if (!redo) {
 #pragma unroll
         for (int j = 0; j < kRound; j++) {
@@ -2045,9 +2079,9 @@ __device__ inline void decode_chunk(const DecArr& d, const uint16_t* lut, const 
 // careful path for anything unusual), with no loads from global memory.
 template <int MODE>
 __device__ inline void decode_chunk_staged(const DecArr& d, const uint16_t* lut,
-                                           const uint32_t* glut, int L, uint64_t c,
-                                           int chunk_log2, const uint32_t* w, uint32_t cw,
-                                           uint32_t* err) {
+                                           const uint32_t* glut, const uint64_t* win, int L,
+                                           uint64_t c, int chunk_log2, const uint32_t* w,
+                                           uint32_t cw, uint32_t* err) {
   const uint64_t C = 1ull << chunk_log2;
   StageReader r{0ull, 0, 0u, cw, w};
   const uint64_t cbeg = c * C, cend = min(d.n, cbeg + C);
@@ -2056,13 +2090,78 @@ __device__ inline void decode_chunk_staged(const DecArr& d, const uint16_t* lut,
   const int P = L <= 4 ? 8 : L <= 8 ? 4 : 2;  // symbols per top-up of the bit buffer
   const uint32_t pmask = (uint32_t)P - 1u;
   const int group_bits = P * L;
+  // window path (MODE 4 with a window table): bytes decoded past a round's 16
+  // are carried into the next one
+  uint64_t carry = 0;
+  int cc = 0;
   for (uint64_t i0 = cbeg; i0 < cend; i0 += kRound) {
     const int cnt = (int)min((uint64_t)kRound, cend - i0);
     uint32_t vals[kRound];
     const uint64_t buf0 = r.buf;
     const int nb0 = r.nb;
     const uint32_t rpos0 = r.rpos;
-    bool redo = cnt < kRound;
+    bool redo = cnt < kRound || (lut == nullptr && win == nullptr);
+    if (MODE == 4 && win) {
+      uint64_t a0 = carry, a1 = 0, a2 = 0;
+      int p = cc;
+      while (!redo && p < kRound) {
+        const bool app = r.nb <= 32 && r.rpos < r.cw;
+        const uint32_t wd = w[min(r.rpos, r.cw - 1u)];
+        const int sh = app ? 32 - r.nb : 0;
+        r.buf |= app ? ((uint64_t)wd << sh) : 0ull;
+        r.nb += app ? 32 : 0;
+        r.rpos += app ? 1u : 0u;
+        const uint64_t e = win[(uint32_t)(r.buf >> (64 - kMW))];
+        const int n = (int)((e >> 48) & 15u), bits = (int)(e >> 52);
+        redo = n == 0 || bits > r.nb;
+        const uint64_t v = redo ? 0ull : (e & 0xFFFFFFFFFFFFull);
+        const int s8 = 8 * (p & 7);
+        const uint64_t lo = v << s8, hi = s8 ? v >> (64 - s8) : 0ull;
+        const bool first = p < 8;
+        a0 |= first ? lo : 0ull;
+        a1 |= first ? hi : lo;
+        a2 |= first ? 0ull : hi;
+        r.buf <<= redo ? 0 : bits;
+        r.nb -= redo ? 0 : bits;
+        p += redo ? 0 : n;
+      }
+      if (!redo) {
+        if (vec) {
+          *(GOut128)((__attribute__((address_space(1))) uint8_t*)d.out + i0) =
+              U32x4{(uint32_t)a0, (uint32_t)(a0 >> 32), (uint32_t)a1, (uint32_t)(a1 >> 32)};
+        } else {
+#pragma unroll
+          for (int j = 0; j < kRound; j++)
+            ((__attribute__((address_space(1))) uint8_t*)d.out)[i0 + j] =
+                (uint8_t)((j < 8 ? a0 : a1) >> (8 * (j & 7)));
+        }
+        carry = a2;
+        cc = p - kRound;
+        continue;
+      }
+      // the careful path: the carried values first, then one code at a time
+      r.buf = buf0;
+      r.nb = nb0;
+      r.rpos = rpos0;
+#pragma unroll
+      for (int j = 0; j < kRound; j++) {
+        vals[j] = 0;
+        if (j < cnt && j < cc) {
+          vals[j] = (uint32_t)(int32_t)(int8_t)(uint8_t)(carry >> (8 * j));
+        } else if (j < cnt) {
+          uint64_t v;
+          if (!decode_symbol(r, lut, glut, L, d, &v)) {
+            atomicOr(err, kErrCorrupt);
+            return;
+          }
+          vals[j] = (uint32_t)out_value<MODE>(v);
+        }
+      }
+      carry = 0;
+      cc = 0;
+      store_round<MODE>(d, vals, cnt, i0, vec);
+      continue;
+    }
     if (!redo) {
 #pragma unroll
       for (int j = 0; j < kRound; j++) {
@@ -2127,7 +2226,9 @@ __device__ inline void decode_chunk_k(int K, const DecArr& d, const uint16_t* lu
 
 // Dynamic LDS: an area of kStageWords words per wave (its chunks' staged
 // payload, or its lanes' rings), then the 16-bit table of 2^lut_log2 entries
-// (lut_log2: the longest code among the launch's arrays); 64 KB at most.
+// (lut_log2: the longest code among the launch's arrays), then, when lut_log2
+// <= kWinLog2Max, the 2^kMW-entry window table of a short-code byte array;
+// 64 KB at most.
 __global__ __launch_bounds__(kThreads) void k_decode_huff(const DecArr* arrs,
                                                           const uint32_t* prefix, int A,
                                                           int chunk_log2,
@@ -2153,6 +2254,14 @@ __global__ __launch_bounds__(kThreads) void k_decode_huff(const DecArr* arrs,
   for (uint32_t i = threadIdx.x; i < (1u << L); i += kThreads) {
     const uint32_t e = src[i], sym = e & 0xFFFFu, l = e >> 16;
     lut[i] = (uint16_t)(sym < (uint32_t)kDirect && l ? (l << 12) | sym : 0u);
+  }
+  // byte arrays with short codes also take the window table, when the
+  // launch's longest code leaves room for it (lut_log2 <= kWinLog2Max)
+  const bool use_win = lut_log2 <= kWinLog2Max && d.mode == 4 && L <= kMW;
+  uint64_t* win_lds = reinterpret_cast<uint64_t*>(lut + (((1u << lut_log2) + 3u) & ~3u));
+  if (use_win) {
+    const uint64_t* wsrc = reinterpret_cast<const uint64_t*>(src + kMOff);
+    for (uint32_t i = threadIdx.x; i < (1u << kMW); i += kThreads) win_lds[i] = wsrc[i];
   }
   __syncthreads();
   // The wave's chunks are consecutive, so their payloads are one range of
@@ -2200,9 +2309,12 @@ __global__ __launch_bounds__(kThreads) void k_decode_huff(const DecArr* arrs,
     const uint32_t* wch = area + (uint32_t)(wbeg - r0);
     const uint32_t cw = (uint32_t)(wend - wbeg);
     switch (d.mode) {
-      case 2: decode_chunk_staged<2>(d, lut, src, L, c, chunk_log2, wch, cw, err); break;
-      case 3: decode_chunk_staged<3>(d, lut, src, L, c, chunk_log2, wch, cw, err); break;
-      default: decode_chunk_staged<4>(d, lut, src, L, c, chunk_log2, wch, cw, err); break;
+      case 2: decode_chunk_staged<2>(d, lut, src, nullptr, L, c, chunk_log2, wch, cw, err); break;
+      case 3: decode_chunk_staged<3>(d, lut, src, nullptr, L, c, chunk_log2, wch, cw, err); break;
+      default:
+        decode_chunk_staged<4>(d, lut, src, use_win ? win_lds : nullptr, L, c, chunk_log2, wch,
+                               cw, err);
+        break;
     }
     return;
   }
@@ -2354,10 +2466,12 @@ void launch_decode(const DecArr* arrs_dev, int A, const uint32_t* huff_prefix_de
   k_lut<<<A, kHT, 0, s>>>(arrs_dev, lut, err);
   if (lut_log2 < 1) lut_log2 = 1;
   if (lut_log2 > kMaxLen) lut_log2 = kMaxLen;
-  const size_t shm = (size_t)kThreads / kWave * kStageWords * 4 + (((size_t)2 << lut_log2) + 3) / 4 * 4;
+  const size_t shm = (size_t)kThreads / kWave * kStageWords * 4 +
+                     ((((size_t)1 << lut_log2) + 3) & ~(size_t)3) * 2 +
+                     (lut_log2 <= kWinLog2Max ? (size_t)8 << kMW : 0);
   if (huff_blocks)
-    launch_timed("decode_huff", bytes, k_decode_huff, huff_blocks, kThreads, shm, s,
-               arrs_dev, huff_prefix_dev, A, chunk_log2, lut, lut_log2, err);
+    launch_timed("decode_huff", bytes, k_decode_huff, huff_blocks, kThreads, shm, s, arrs_dev,
+                 huff_prefix_dev, A, chunk_log2, lut, lut_log2, err);
   if (fixed_blocks)
     launch_timed("decode_fixed", bytes, k_decode_fixed, fixed_blocks, kThreads, 0, s,
                arrs_dev, fixed_prefix_dev, A, err);
