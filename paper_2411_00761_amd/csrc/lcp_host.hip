@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <initializer_list>
+#include <algorithm>
 #include <vector>
 
 #include "../../include/lcp.h"
@@ -1072,6 +1073,14 @@ constexpr int kMaxBatchArrays = kMaxBatchFrames * kMaxF + 2;
 // Decode one group of arrays (descriptors staged at arrtab_host[base..base+A))
 // through the batched kernels; the LUT slots start at array `base`.
 lcp_status decode_arrays(lcp_plan_s* P, int base, int A, int cl, uint64_t bytes, hipStream_t s) {
+  // Huffman arrays with the most bits per value first: a chunk is decoded by
+  // one lane from start to end, so their workgroups take longest, and started
+  // first they overlap the rest instead of trailing the launch
+  auto density = [](const DecArr& d) {
+    return d.coder == 1 && d.n ? (double)d.nbytes / (double)d.n : -1.0;
+  };
+  std::stable_sort(P->arrtab_host + base, P->arrtab_host + base + A,
+                   [&](const DecArr& x, const DecArr& y) { return density(x) > density(y); });
   uint32_t* hp = P->prefix_host + 2 * base;
   uint32_t* fp = hp + A;
   uint32_t hb = 0, fb = 0;
