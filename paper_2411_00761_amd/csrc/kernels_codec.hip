@@ -2377,7 +2377,10 @@ uint32_t enc_chunk_blocks(uint64_t n, int chunk_log2, bool bytes) {
 uint32_t enc_copy_blocks(uint64_t n, int chunk_log2) {
   return gclamp((n + (1ull << chunk_log2) - 1) >> chunk_log2, 256);
 }
-uint32_t enc_fixed_blocks(uint64_t n) { return gclamp((n + 2047) / 2048, 1024); }
+// Fixed-length packing loops over its words, so a few workgroups per array
+// suffice; every emit workgroup of a single record also lays the record out,
+// which workgroups that find their array Huffman-coded would only repeat.
+uint32_t enc_fixed_blocks(uint64_t n) { return gclamp((n + 2047) / 2048, 128); }
 
 uint32_t enc_slot_words(bool is64, int chunk_log2) {
   // per symbol at most the longest code and, for values from kDirect up, one
