@@ -1393,12 +1393,20 @@ __device__ inline uint32_t pack_chunk_wave(uint32_t c, const ByteRun<RUN>& b, GW
 // whose bytes start 16-byte aligned load with vector loads, the next chunk's
 // while one is packed; the ragged last chunk (and every chunk otherwise) loads
 // byte by byte.
+// With `build` (temporal records of a run) every workgroup first builds the
+// array's code itself from the residual kernel's spread histogram copies, as
+// the one-wave builder of k_huff_build does (wave h tries h halvings), so
+// that no build launch sits between the residuals and the packing; workgroup
+// 0 of the array stores what the emit needs (used-symbol table, sizes,
+// candidate flag).  An array with symbols past kWave flags kErrRebuild.
 template <int RUN>
 __global__ __launch_bounds__(kThreads) void k_pack_wave(const EncArr* E, ArrWork* W,
                                                         const uint32_t* pre, int NA,
                                                         int chunk_log2, uint32_t* cnt,
                                                         uint32_t* stage, uint32_t slot,
-                                                        uint32_t* err) {
+                                                        uint32_t* err, const uint32_t* hpart,
+                                                        const unsigned long long* hmax,
+                                                        int build) {
   extern __shared__ uint32_t bufs[];
   __shared__ uint32_t lc[kPackLcLds];
   __shared__ unsigned long long wsum[kPackWaves];
@@ -1408,9 +1416,9 @@ __global__ __launch_bounds__(kThreads) void k_pack_wave(const EncArr* E, ArrWork
   const EncArr& e = E[a];
   // the table's first kPackLcLds entries, requested with the array's fields
   // (entries past the largest value's symbol are never looked up)
-  const uint32_t lc_t = ((GWordsIn)w.lc)[threadIdx.x];
-  if (!w.cand) return;
-  const uint64_t n = w.n;
+  const uint32_t lc_t = build ? 0u : ((GWordsIn)w.lc)[threadIdx.x];
+  if (!build && !w.cand) return;
+  const uint64_t n = build ? arr_len(e.in) : (uint64_t)w.n;
   const uint8_t* v = static_cast<const uint8_t*>(e.in.v);
   GWordsIn esc = (GWordsIn)e.in.esc;
   GWordsIn lc_glb = (GWordsIn)w.lc;
@@ -1441,7 +1449,105 @@ __global__ __launch_bounds__(kThreads) void k_pack_wave(const EncArr* E, ArrWork
                                     : lane_off,
                           q[k]);
   }
-  lc[threadIdx.x] = swap_halves(lc_t);
+  if (build) {
+    __shared__ uint32_t s_cb[kWave], s_mdb[kPackWaves], s_cand;
+    __shared__ unsigned long long s_mx;
+    __shared__ uint64_t s_scr[kPackWaves][kWave];
+    const uint32_t copies = e.copies, copy0 = e.copy0;
+    const int lane = lane_id();
+    lc[threadIdx.x] = 0;  // symbols past the alphabet: never looked up
+    if (wave_id() == 0) {
+      // largest value over the copies; counts of symbols below kWave (bins
+      // past the largest symbol are zero: every build clears what it used)
+      unsigned long long m = (uint32_t)lane < copies ? hmax[copy0 + lane] : 0ull;
+#pragma unroll
+      for (int d = kWave / 2; d > 0; d >>= 1) {
+        const unsigned long long o = shfl_xor_u64(m, d);
+        m = o > m ? o : m;
+      }
+      uint32_t x[kHistCopies];
+#pragma unroll
+      for (int c = 0; c < kHistCopies; c++)
+        x[c] = (uint32_t)c < copies ? hpart[(uint64_t)(copy0 + c) * kAlphabet + lane] : 0u;
+      uint32_t sum = 0;
+#pragma unroll
+      for (int c = 0; c < kHistCopies; c++) sum += x[c];
+      s_cb[lane] = sum;
+      if (lane == 0) s_mx = m;
+    }
+    __syncthreads();
+    const unsigned long long mx = s_mx;
+    if (n == 0 || sym_bound(mx) + 1 > kWave) {
+      // the array is laid out as fixed length meanwhile (its fields within
+      // its input) and the frame is coded again
+      if (threadIdx.x == 0) {
+        atomicOr(err, kErrRebuild);
+        if (lb == 0) {
+          w.U = 0;
+          w.L = 0;
+          w.maxv = mx;
+          w.n = (uint32_t)n;
+          w.nchunks = nchunks;
+          w.huff_bits = 0;
+          w.cand = 0;
+        }
+      }
+      return;
+    }
+    const uint32_t c = s_cb[lane];
+    uint32_t len;
+    uint32_t md = small_lengths(c, wave_id(), &len, s_scr[wave_id()]);
+    if (lane == 0) s_mdb[wave_id()] = md;
+    __syncthreads();
+    int pick = -1;
+    for (int h = 0; h < kPackWaves && pick < 0; h++)
+      if (s_mdb[h] <= (uint32_t)kMaxLen) pick = h;
+    if (pick < 0) pick = 0;  // wave 0 goes on halving, one count at a time
+    if ((int)wave_id() == pick) {
+      for (int h = kPackWaves; md > (uint32_t)kMaxLen && h < kHalvings; h++)
+        md = small_lengths(c, h, &len, s_scr[pick]);
+      // canonical codes (shorter first, ties by symbol), as small_codes
+      const uint64_t used = __ballot(c != 0);
+      const uint32_t U = (uint32_t)__popcll(used);
+      uint32_t first = 0, before = 0, code = 0;
+      for (uint32_t l = 1; l <= (uint32_t)kMaxLen; l++) {
+        const uint32_t prev = l > 1 ? (uint32_t)__popcll(__ballot(len == l - 1)) : 0u;
+        code = (code + prev) << 1;
+        if (len == l) first = code;
+      }
+      const uint64_t lt = lanemask_lt();
+      for (uint32_t l = 1; l <= (uint32_t)kMaxLen; l++) {
+        const uint64_t m = __ballot(len == l);
+        if (len == l) before = (uint32_t)__popcll(m & lt);
+      }
+      uint32_t lmax = len;
+      unsigned long long bits = (unsigned long long)c * len;
+#pragma unroll
+      for (int d = kWave / 2; d > 0; d >>= 1) {
+        lmax = max(lmax, (uint32_t)__shfl_xor((int)lmax, d, kWave));
+        bits += shfl_xor_u64(bits, d);
+      }
+      lc[lane] = c ? (len | ((first + before) << 16)) : 0u;  // length in the low half
+      const uint32_t cand = huff_candidate(U, n, mx, bits, chunk_log2);
+      if (lb == 0) {
+        if (c) w.table[(uint32_t)__popcll(used & lt)] = (uint32_t)lane | (len << 16);
+        if (lane == 0) {
+          w.U = U;
+          w.L = lmax;
+          w.maxv = mx;
+          w.n = (uint32_t)n;
+          w.nchunks = nchunks;
+          w.huff_bits = bits;
+          w.cand = cand;
+        }
+      }
+      if (lane == 0) s_cand = cand;
+    }
+    __syncthreads();
+    if (!s_cand) return;
+  } else {
+    lc[threadIdx.x] = swap_halves(lc_t);
+  }
   __syncthreads();
   if constexpr (RUN >= 4) {
     if (deep) {
@@ -1588,7 +1694,8 @@ __global__ __launch_bounds__(kThreads) void k_emit(const EncArr* E, ArrWork* W, 
                                                    uint32_t slot64, uint8_t* out, uint64_t cap,
                                                    unsigned long long* offs,
                                                    const unsigned long long* base_dev,
-                                                   uint32_t* err) {
+                                                   uint32_t* err, uint32_t* clear_part,
+                                                   unsigned long long* clear_max) {
   const bool fixed = blockIdx.x < fixed_blocks;
   const uint32_t b = fixed ? blockIdx.x : blockIdx.x - fixed_blocks;
   const uint32_t* pre = fixed ? pre_fixed : pre_copy;
@@ -1637,6 +1744,14 @@ __global__ __launch_bounds__(kThreads) void k_emit(const EncArr* E, ArrWork* W, 
   } else {
     const ArrWork& w = W[a];
     pl = ArrPlace{w.coder, w.w, out + recs[E[a].rec].off + w.off, !(*err & kErrCapacity)};
+  }
+  // a record whose packing built its code: the histogram copies (symbols below
+  // kWave, which are all it used) start from zero for the next residuals
+  if (clear_part && fixed && lb == 0) {
+    const uint32_t copies = E[a].copies, copy0 = E[a].copy0;
+    for (uint32_t i = threadIdx.x; i < copies * kWave; i += kThreads)
+      clear_part[(uint64_t)(copy0 + i / kWave) * kAlphabet + i % kWave] = 0;
+    if (threadIdx.x < copies) clear_max[copy0 + threadIdx.x] = 0;
   }
   if (fixed)
     pack_fixed_block(E, W, a, pl, lb, nb);
@@ -2406,8 +2521,10 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
   // codes only run for arrays whose plain build is too deep.  Temporal residual
   // arrays (hist_done) halve inline: their alphabets are short and the fallback
   // launches would cost more than they save.
-  launch_timed("huff_build", 0, k_huff_build, NA, kHT, 0, s, L.arrs, X.hist_part, X.hist_max,
-               work, X.huff_lens, X.huff_maxd, hist_done ? 1 : 0, chunk_log2);
+  const int fused = L.fused && L.all_bytes && pack_by_wave(chunk_log2);
+  if (!fused)
+    launch_timed("huff_build", 0, k_huff_build, NA, kHT, 0, s, L.arrs, X.hist_part, X.hist_max,
+                 work, X.huff_lens, X.huff_maxd, hist_done ? 1 : 0, chunk_log2);
   if (!hist_done) {
     k_huff_lengths<<<dim3(NA, kHalvings - 1), kHT, 0, s>>>(work, X.huff_lens, X.huff_maxd);
     k_huff_codes<<<NA, kHT, 0, s>>>(L.arrs, work, X.huff_lens, X.huff_maxd, chunk_log2);
@@ -2425,7 +2542,8 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
       default: break;
     }
     launch_timed("pack_huff", L.values * 6ull, kernel, L.chunk_blocks, kThreads, shm, s, L.arrs,
-                 work, pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, err);
+                 work, pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, err,
+                 X.hist_part, X.hist_max, fused);
   } else {
     const size_t shm = (size_t)slot64 * 4;
     const uint32_t g = L.chunk_blocks;
@@ -2448,7 +2566,8 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
   if (emit_blocks)
     launch_timed("emit", L.values * 6ull, k_emit, emit_blocks, kThreads, 0, s, L.arrs, work,
                  L.recs, L.rec0, fold, pre_fixed, L.fixed_blocks, pre_copy, NA, X.chunk_words,
-                 X.stage, slot32, slot64, out, cap, offs, base, err);
+                 X.stage, slot32, slot64, out, cap, offs, base, err,
+                 fused ? X.hist_part : nullptr, fused ? X.hist_max : nullptr);
 }
 
 uint32_t decode_blocks(const DecArr& d, int chunk_log2, bool huff) {

@@ -230,13 +230,17 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
                                                       uint32_t* v_res, int32_t* q_new,
                                                       uint32_t* err, int vec,
                                                       uint32_t* hist_part,
-                                                      unsigned long long* hist_max) {
+                                                      unsigned long long* hist_max,
+                                                      ArrWork* zw) {
   // per field and wave kResPriv private bins, sized by F at launch so that
   // LDS does not cap the workgroups resident per CU
   extern __shared__ uint32_t bins_lds[];
   __shared__ uint32_t smax[kMaxF][kThreads / kWave];
   auto bins = [&](int f, int w) { return bins_lds + ((uint32_t)f * (kThreads / kWave) + w) * kResPriv; };
   for (int j = threadIdx.x; j < F * (kThreads / kWave) * kResPriv; j += kThreads) bins_lds[j] = 0;
+  // the coder's word totals start from zero (the frame before was emitted)
+  if (zw && blockIdx.x == 0 && threadIdx.x < (uint32_t)(F * kWordParts))
+    zw[threadIdx.x / kWordParts].huff_words[threadIdx.x % kWordParts] = 0;
   __syncthreads();
   const int copy = blockIdx.x % kHistCopies;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -1035,13 +1039,14 @@ inline bool al16(const void* p) { return ((uintptr_t)p & 15) == 0; }
 void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
                     const uint32_t* perm_ref, const int32_t* q_ref, uint8_t* v8, uint32_t* v_res,
                     int32_t* q_new, uint32_t* err, uint32_t* hist_part,
-                    unsigned long long* hist_max, hipStream_t s) {
+                    unsigned long long* hist_max, ArrWork* zero_words, hipStream_t s) {
   const int vec = (n % 4 == 0) && al16(perm_ref) && al16(q_ref) && al16(v_res) && al16(q_new) &&
                   (!v8 || al16(v8));
   // algorithmic bytes: permutation, x and reference codes read; residuals
   // (bytes, or u32) and new codes written
   launch_timed("t_resid", n * (4 + 12ull * F + (v8 ? 1ull : 4ull) * F), k_t_resid, grid_for(vec ? n / 4 : n, kThreads * 2, 2048), kThreads, (size_t)F * (kThreads / kWave) * kResPriv * 4, s,
-               x, F, n, g, perm_ref, q_ref, v8, v_res, q_new, err, vec, hist_part, hist_max);
+               x, F, n, g, perm_ref, q_ref, v8, v_res, q_new, err, vec, hist_part, hist_max,
+               zero_words);
 }
 
 void launch_t_codes(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,

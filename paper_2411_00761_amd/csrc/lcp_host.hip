@@ -114,6 +114,9 @@ struct lcp_plan_s {
   uint32_t* err;  // the error word (low half of ret_dev[0])
   bool err_clean = false;  // the error word is known to be zero at the stream's tail
   int run_len = kTRunStart;  // frames the next temporal run may take
+  // temporal frames left to code with the separate code build, after a frame
+  // whose residual alphabet outgrew the packing kernel's own build
+  int fuse_skip = 0;
   // temporal runs (frames coded back to back, one read-back per run): per
   // frame [4k] error word, [4k + 1, 4k + 3) record start and end
   unsigned long long *run_dev, *run_host;
@@ -384,6 +387,7 @@ struct EncBuild {
   uint32_t copies = 0;
   uint64_t cw = 0, values = 0, stage = 0;
   std::vector<uint32_t> hb, cb, fb, kb;
+  bool fused = false;  // the packing builds the code (temporal record, a chunk per wave)
 };
 
 // Adds one array of at most nb values to record rec; copy0 < 0 places its
@@ -455,6 +459,7 @@ lcp_status enc_launch(lcp_plan_s* P, EncBuild& B, uint8_t* out, uint64_t cap, bo
   L.copy_blocks = k;
   L.values = B.values;
   L.all_bytes = 1;
+  L.fused = B.fused ? 1 : 0;
   for (int a = 0; a < NA; a++) L.all_bytes &= P->earr_host[a].in.esc != nullptr ? 1 : 0;
   // A single record travels to the layout kernel as an argument; the array and
   // prefix tables are not uploaded again while the device holds the same bytes
@@ -682,10 +687,16 @@ lcp_status launch_t(lcp_plan_s* P, const float* const* x, uint64_t n, const RefS
                     uint64_t seq, uint8_t* out, uint64_t cap, int32_t* q_new, uint32_t* err,
                     unsigned long long* offs, const unsigned long long* base, hipStream_t s) {
   const int F = P->F;
+  // residual alphabets are short: unless one recently was not, the packing
+  // kernel builds the code (the residual kernel zeroes the word totals)
+  const bool fused = P->fuse_skip == 0 && n > 0 && P->chunk_log2 >= 6 && P->chunk_log2 <= 10;
+  if (P->fuse_skip > 0) P->fuse_skip--;
   launch_t_resid(field_ptrs(x, F), F, n, t_grid(ref, F), P->ppool[ref.perm], P->qpool[ref.q],
-                 P->v_byte, P->v_slot, q_new, err, P->hist_part, P->hist_max, s);
+                 P->v_byte, P->v_slot, q_new, err, P->hist_part, P->hist_max,
+                 fused ? P->work : nullptr, s);
   EncBuild B;
   B.R = 1;
+  B.fused = fused;
   EncRec& rc = P->erec_host[0];
   memset(&rc, 0, sizeof(rc));
   rc.h = make_hdr(1, F, 0, P->chunk_log2, F, n, seq, ref.seq, ref.grid);
@@ -700,6 +711,16 @@ lcp_status launch_t(lcp_plan_s* P, const float* const* x, uint64_t n, const RefS
   return enc_launch(P, B, out, cap, true, s, err, offs, base);
 }
 
+// After a temporal frame whose packing could not build its code (an alphabet
+// past one wave's): its histogram copies hold counts past the bins the emit
+// clears, so all are cleared, and the next frames use the separate build.
+constexpr int kFuseBackoff = 64;
+void fused_fallback(lcp_plan_s* P, hipStream_t s) {
+  launch_fill_u32(P->hist_part, P->hist_copies * kAlphabet, 0u, s);
+  launch_fill_u32(reinterpret_cast<uint32_t*>(P->hist_max), 2 * P->hist_copies, 0u, s);
+  P->fuse_skip = kFuseBackoff;
+}
+
 lcp_status compress_t(lcp_plan_s* P, const float* const* x, uint64_t n, const RefState& ref,
                       uint64_t seq, uint8_t* out, uint64_t cap, int32_t* q_new, uint64_t* size,
                       hipStream_t s) {
@@ -709,6 +730,17 @@ lcp_status compress_t(lcp_plan_s* P, const float* const* x, uint64_t n, const Re
   uint32_t flags = 0;
   uint64_t offs[2] = {0, 0};
   st = finish_records(P, 1, offs, &flags, s);
+  if (flags & kErrRebuild) {
+    fused_fallback(P, s);
+    if (!(flags & (kErrNonFinite | kErrRange))) {
+      // the frame again, with the separate build
+      clear_err(P, s);
+      if ((st = launch_t(P, x, n, ref, seq, out, cap, q_new, P->err, P->offs_dev, nullptr, s)))
+        return st;
+      flags = 0;
+      st = finish_records(P, 1, offs, &flags, s);
+    }
+  }
   *size = offs[1];
   if (flags & kErrNonFinite) return LCP_ERR_ARG;
   if (flags & kErrRange) return LCP_ERR_RANGE;
@@ -959,6 +991,13 @@ lcp_status run_t(lcp_plan_s* P, const lcp_frame_in* fr, int D, const RunFrame* r
   }
   HIP_OK(hipMemcpyAsync(P->run_host, P->run_dev, 32ull * D, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
+  // a frame flagged for the separate build ends the commits there; the
+  // per-frame path codes it again
+  for (int k = 0; k < D; k++)
+    if ((uint32_t)(P->run_host[4 * k] & 0xFFFFFFFFull) & kErrRebuild) {
+      fused_fallback(P, s);
+      break;
+    }
   int c = 0;
   for (; c < D; c++) {
     const uint32_t flags = (uint32_t)(P->run_host[4 * c] & 0xFFFFFFFFull);

@@ -137,6 +137,9 @@ enum : uint32_t {
   kErrCorrupt = 2u,
   kErrCapacity = 4u,
   kErrRange = 8u,  // a temporal frame left its reference grid's range
+  // a temporal frame whose packing was to build its own code found an alphabet
+  // beyond one wave's (the frame is coded again with the separate build)
+  kErrRebuild = 16u,
 };
 
 // ---- kernel timer (lcp_host.hip) ----
@@ -229,7 +232,7 @@ void launch_s_recon_b(const uint32_t* blk, const uint32_t* corner, const uint32_
 void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
                     const uint32_t* perm_ref, const int32_t* q_ref, uint8_t* v8, uint32_t* v_res,
                     int32_t* q_new, uint32_t* err, uint32_t* hist_part,
-                    unsigned long long* hist_max, hipStream_t s);
+                    unsigned long long* hist_max, ArrWork* zero_words, hipStream_t s);
 void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, uint64_t B,
                      uint64_t n, uint64_t total_blocks, const uint32_t* bn, int k,
                      uint32_t* corner, uint32_t* mark, uint32_t* err, hipStream_t s);
@@ -291,6 +294,9 @@ struct EncLaunch {
   uint32_t hist_blocks, chunk_blocks, fixed_blocks, copy_blocks;
   uint64_t values;  // sum of the arrays' lengths (bounds), for the kernel timer
   int all_bytes;    // every array holds bytes with escapes (temporal residuals)
+  // temporal record whose packing builds the code itself (all_bytes, a chunk
+  // per wave): no build launch; the emit clears the histogram copies
+  int fused;
 };
 // Coding scratch of a launch set: a word count per chunk and the staging of
 // the Huffman payloads before they move into their records.

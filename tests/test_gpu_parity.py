@@ -339,3 +339,39 @@ def test_temporal_sixty_symbols(lcp):
         resid.append(r)
     P = temporal_pair(lcp, n, 10, resid, seed=502)
     assert all(d["coder"] == 1 and d["used"] == 63 for d in P["dirs"])
+
+
+def test_temporal_run_with_one_wide_frame(lcp):
+    """Forced temporal frames coded in one call (back-to-back runs), one of
+    them with residuals far past 64 symbols: the frames before it, that frame
+    and the many after it (those first with the separate code build, later
+    again with the packing kernel building the code) all match the oracle."""
+    n, frames, wide, cl = 6000, 80, 5, 7
+    rng = np.random.default_rng(611)
+    x0 = datagen.uniform_frame(n, hi=50.0, seed=612)
+    grids = O.grids_for(x0, O.EB_ABS, 1e-3)
+    q = [O.quantize(x0[f], grids[f]) for f in range(3)]
+    xs = [x0]
+    for t in range(1, frames):
+        x = np.empty_like(x0)
+        for f in range(3):
+            r = rng.integers(-2, 3, size=n)
+            if t == wide:
+                far = rng.random(n) < 0.01
+                r[far] = rng.integers(-3000, 3000, size=int(far.sum()))
+            q[f] = q[f] + r
+            x[f] = O.reconstruct(q[f], grids[f])
+        xs.append(x)
+    ost = O.Stream(O.EB_ABS, 1e-3, batch_size=0, block_log2=6, chunk_log2=cl, max_n=n)
+    plan = lcp.Plan(1e-3, lcp.EB_ABS, multi_frame=True, batch_size=0, block_log2=6, chunk_log2=cl,
+                    max_particles=n)
+    methods = [O.METHOD_S] + [O.METHOD_T] * (frames - 1)
+    out, offs, used, _ = plan.compress([torch.from_numpy(x).cuda() for x in xs], methods=methods)
+    assert list(used) == methods
+    for t, x in enumerate(xs):
+        want, wused, _ = ost.compress(x, method=methods[t])
+        assert wused == methods[t], t
+        rec = out[offs[t]:offs[t + 1]].cpu().numpy().tobytes()
+        assert rec == want, f"frame {t}: " + diff_report(rec, want)
+        if t == wide:
+            assert max(d["param"] for d in fmt_ref.parse(want)["dirs"]) > 6
