@@ -809,6 +809,8 @@ __global__ __launch_bounds__(kThreads) void k_t_recon(const int32_t* q_ref, int 
 // first against q_ref): per slot the codes stay in registers while each
 // frame's residuals (int32, decoded in place in its output arrays) are added
 // and its float32 values written; only the last frame's codes are stored.
+constexpr int kChainGroup = 8;  // frames of a chain whose residuals load together
+
 __global__ __launch_bounds__(kThreads) void k_t_recon_chain(const int32_t* q_ref, int F,
                                                             uint64_t n, GridDev g, ChainOut out,
                                                             int J, int32_t* q_last, uint32_t* err,
@@ -821,37 +823,71 @@ __global__ __launch_bounds__(kThreads) void k_t_recon_chain(const int32_t* q_ref
       for (int f = 0; f < F; f++) {
         const int4 qr = reinterpret_cast<const int4*>(q_ref + (uint64_t)f * n)[s4];
         int64_t q[4] = {qr.x, qr.y, qr.z, qr.w};
-        for (int j = 0; j < J; j++) {
-          float4* o = reinterpret_cast<float4*>(out.p[j][f]) + s4;
-          int32_t rr[4];
-          if (out.r8[j][f]) {
-            const uint32_t b = reinterpret_cast<const uint32_t*>(out.r8[j][f])[s4];
-#pragma unroll
-            for (int u = 0; u < 4; u++) {
-              rr[u] = (int32_t)(int8_t)(uint8_t)(b >> (8 * u));
-              if (rr[u] == -128) rr[u] = reinterpret_cast<const int32_t*>(o)[u];
-            }
-          } else {
-            const int4 r = *reinterpret_cast<const int4*>(o);
-            rr[0] = r.x;
-            rr[1] = r.y;
-            rr[2] = r.z;
-            rr[3] = r.w;
-          }
-          q[0] += rr[0];
-          q[1] += rr[1];
-          q[2] += rr[2];
-          q[3] += rr[3];
+        // one frame of the chain: rr holds its four residuals
+        auto step = [&](int j, const int32_t* rr) {
           float v[4];
 #pragma unroll
           for (int u = 0; u < 4; u++) {
+            q[u] += rr[u];
             if (q[u] < -(int64_t)kQLimit || q[u] >= (int64_t)kQLimit) {
               bad = 1;
               q[u] = 0;
             }
             v[u] = reconstruct(q[u], g.eb_q[f], g.m[f]);
           }
-          *o = make_float4(v[0], v[1], v[2], v[3]);
+          reinterpret_cast<float4*>(out.p[j][f])[s4] = make_float4(v[0], v[1], v[2], v[3]);
+        };
+        for (int j0 = 0; j0 < J; j0 += kChainGroup) {
+          const int G = min(kChainGroup, J - j0);
+          bool bytes = true;
+          for (int k = 0; k < G; k++) bytes = bytes && out.r8[j0 + k][f] != nullptr;
+          uint32_t bw[kChainGroup];
+          uint32_t esc = 0;
+          if (bytes) {
+            // the group's residual words are requested together (a store to
+            // one frame's output could alias the next frame's residuals, so
+            // loads issued frame by frame would each wait for memory in turn)
+#pragma unroll
+            for (int k = 0; k < kChainGroup; k++)
+              bw[k] = reinterpret_cast<const uint32_t*>(out.r8[j0 + min(k, G - 1)][f])[s4];
+#pragma unroll
+            for (int k = 0; k < kChainGroup; k++) {
+              const uint32_t x = bw[k] ^ 0x80808080u;  // a zero byte: an escape (-128)
+              if (k < G) esc |= (x - 0x01010101u) & ~x & 0x80808080u;
+            }
+          }
+          if (bytes && __ballot(esc != 0) == 0) {
+            // no escapes in the wave: no loads between the stores
+#pragma unroll
+            for (int k = 0; k < kChainGroup; k++) {
+              if (k >= G) break;
+              int32_t rr[4];
+#pragma unroll
+              for (int u = 0; u < 4; u++) rr[u] = (int32_t)(int8_t)(uint8_t)(bw[k] >> (8 * u));
+              step(j0 + k, rr);
+            }
+          } else {
+            for (int k = 0; k < G; k++) {
+              const int j = j0 + k;
+              const int32_t* o = reinterpret_cast<const int32_t*>(out.p[j][f]) + 4 * s4;
+              int32_t rr[4];
+              if (out.r8[j][f]) {
+                const uint32_t b = reinterpret_cast<const uint32_t*>(out.r8[j][f])[s4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                  rr[u] = (int32_t)(int8_t)(uint8_t)(b >> (8 * u));
+                  if (rr[u] == -128) rr[u] = o[u];  // escaped: the int32 residual
+                }
+              } else {
+                const int4 r = *reinterpret_cast<const int4*>(o);
+                rr[0] = r.x;
+                rr[1] = r.y;
+                rr[2] = r.z;
+                rr[3] = r.w;
+              }
+              step(j, rr);
+            }
+          }
         }
         if (q_last)
           reinterpret_cast<int4*>(q_last + (uint64_t)f * n)[s4] =

@@ -375,3 +375,12 @@ def test_temporal_run_with_one_wide_frame(lcp):
         assert rec == want, f"frame {t}: " + diff_report(rec, want)
         if t == wide:
             assert max(d["param"] for d in fmt_ref.parse(want)["dirs"]) > 6
+    # decoded in one call: chains of up to 16 temporal frames, one of them
+    # with escaped residuals
+    dplan = lcp.Plan(1e-3, lcp.EB_ABS, multi_frame=True, batch_size=0, block_log2=6,
+                     chunk_log2=cl, max_particles=n)
+    dec = dplan.decompress(out, offs)
+    dst = O.Stream(O.EB_ABS, 1e-3, batch_size=0, block_log2=6, chunk_log2=cl, max_n=n)
+    for t in range(frames):
+        w = dst.decompress(out[offs[t]:offs[t + 1]].cpu().numpy().tobytes())
+        assert all(bits_equal(dec[t][f].cpu().numpy(), w[f]) for f in range(3)), t
