@@ -177,16 +177,23 @@ class Plan:
         """Returns (out uint8 tensor, offsets list, methods_used list, perms list|None)."""
         import torch
         nf = len(frames)
-        frames = [f.contiguous() for f in frames]
+        frames = [f if f.is_contiguous() else f.contiguous() for f in frames]
         arr = (lcp_frame_in * nf)()
         cap = 0
+        bounds = {}
+        # field k of a contiguous (F, n) frame starts k rows after the first
+        # (pointer arithmetic: indexing a tensor per field costs microseconds)
         for j, f in enumerate(frames):
             assert f.dtype == torch.float32 and f.is_cuda and f.shape[0] == self.F
+            base, n = f.data_ptr(), f.shape[1]
             for k in range(self.F):
-                arr[j].fields[k] = f[k].data_ptr()
-            arr[j].n = f.shape[1]
+                arr[j].fields[k] = base + 4 * n * k
+            arr[j].n = n
             arr[j].method = METHOD_AUTO if methods is None else methods[j]
-            cap += (self.bound(f.shape[1]) + 3) & ~3
+            b = bounds.get(n)
+            if b is None:
+                b = bounds[n] = (self.bound(n) + 3) & ~3
+            cap += b
         if out is None:
             out = torch.empty(max(cap, 4), dtype=torch.uint8, device=f"cuda:{self.device}")
         offs = (C.c_uint64 * (nf + 1))()
@@ -207,9 +214,11 @@ class Plan:
         """Decode records at buf[offsets[j]:offsets[j+1]]; returns (F, n) float32 tensors."""
         import torch
         nf = len(offsets) - 1
+        offsets = [int(o) for o in offsets]
         blobs = (lcp_blob * nf)()
+        base = buf.data_ptr()
         for j in range(nf):
-            blobs[j].data = buf.data_ptr() + offsets[j]
+            blobs[j].data = base + offsets[j]
             blobs[j].size = (sizes[j] if sizes is not None else offsets[j + 1] - offsets[j])
         if outs is None:
             outs = []
@@ -218,13 +227,15 @@ class Plan:
                 outs.append(torch.empty((self.F, n), dtype=torch.float32, device=buf.device))
         fo = (lcp_frame_out * nf)()
         for j, o in enumerate(outs):
+            ob, row = o.data_ptr(), 4 * o.stride(0)
+            assert o.dtype == torch.float32 and o.stride(1) == 1
             for k in range(self.F):
-                fo[j].fields[k] = o[k].data_ptr()
+                fo[j].fields[k] = ob + row * k
             fo[j].capacity = o.shape[1]
         n_out = (C.c_uint64 * max(nf, 1))()
         _check(lib().lcp_decompress(self.h, nf, blobs, fo, n_out, _stream_handle()),
                "lcp_decompress")
-        return [o[:, : int(n_out[j])] for j, o in enumerate(outs)]
+        return [o if o.shape[1] == n_out[j] else o[:, : int(n_out[j])] for j, o in enumerate(outs)]
 
     @staticmethod
     def record_n(buf, offset: int) -> int:
@@ -309,10 +320,12 @@ class Server:
         rq = lcp_request()
         rq.kind = REQ_COMPRESS
         rq.stream = stream
-        frame = frame.contiguous()
+        if not frame.is_contiguous():
+            frame = frame.contiguous()
+        base, n = frame.data_ptr(), frame.shape[1]
         for k in range(self.F[stream]):
-            rq.frame.fields[k] = frame[k].data_ptr()
-        rq.frame.n = frame.shape[1]
+            rq.frame.fields[k] = base + 4 * n * k
+        rq.frame.n = n
         rq.frame.method = method
         rq.out = out.data_ptr()
         rq.out_cap = out.numel()
@@ -325,8 +338,10 @@ class Server:
         rq.stream = stream
         rq.blob.data = buf.data_ptr() + offset
         rq.blob.size = size
+        assert out.is_floating_point() and out.element_size() == 4 and out.stride(1) == 1
+        ob, row = out.data_ptr(), 4 * out.stride(0)
         for k in range(self.F[stream]):
-            rq.dst.fields[k] = out[k].data_ptr()
+            rq.dst.fields[k] = ob + row * k
         rq.dst.capacity = out.shape[1]
         return self._submit(rq, (buf, out))
 
