@@ -10,6 +10,8 @@ import ctypes as C
 import os
 from typing import Sequence
 
+import numpy as np
+
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liblcp_hip.so")
 
@@ -53,6 +55,53 @@ class lcp_blob(C.Structure):
 
 class lcp_frame_out(C.Structure):
     _fields_ = [("fields", C.c_void_p * MAX_FIELDS), ("capacity", C.c_uint64)]
+
+
+# the descriptor arrays are filled as u64 tables of these widths
+_FRAME_IN_WORDS = C.sizeof(lcp_frame_in) // 8
+_FRAME_OUT_WORDS = C.sizeof(lcp_frame_out) // 8
+assert C.sizeof(lcp_frame_in) == 8 * (MAX_FIELDS + 2) and C.sizeof(lcp_blob) == 16
+assert C.sizeof(lcp_frame_out) == 8 * (MAX_FIELDS + 1)
+
+
+# Descriptor arrays for a call, filled as one u64 table each (setting ctypes
+# fields, or indexing a tensor, per field costs microseconds, i.e. hundreds on
+# a call of many frames).  Each returns the ctypes array and the table that
+# backs it (keep the table alive for the call).
+def frame_in_table(frames, F, methods=None):
+    """lcp_frame_in per contiguous (F, n) frame: field k starts k rows after the first."""
+    nf = len(frames)
+    base = np.array([f.data_ptr() for f in frames], np.uint64)
+    ns = np.array([f.shape[1] for f in frames], np.uint64)
+    tab = np.zeros((nf, _FRAME_IN_WORDS), np.uint64)
+    for k in range(F):
+        tab[:, k] = base + np.uint64(4 * k) * ns
+    tab[:, MAX_FIELDS] = ns
+    tab[:, MAX_FIELDS + 1] = (METHOD_AUTO if methods is None
+                              else np.asarray(methods, np.int64).astype(np.uint64))
+    return (lcp_frame_in * nf).from_buffer(tab), tab
+
+
+def blob_table(base, offsets, sizes=None):
+    """lcp_blob per record buf[offsets[j]:offsets[j+1]] (or of sizes[j] bytes)."""
+    ofs = np.asarray(offsets, np.uint64)
+    nf = len(offsets) - 1
+    tab = np.empty((nf, 2), np.uint64)
+    tab[:, 0] = np.uint64(base) + ofs[:-1]
+    tab[:, 1] = np.asarray(sizes, np.uint64)[:nf] if sizes is not None else ofs[1:] - ofs[:-1]
+    return (lcp_blob * nf).from_buffer(tab), tab
+
+
+def frame_out_table(outs, F):
+    """lcp_frame_out per (F, n) output with unit column stride."""
+    nf = len(outs)
+    ob = np.array([o.data_ptr() for o in outs], np.uint64)
+    row = np.array([o.element_size() * o.stride(0) for o in outs], np.uint64)
+    tab = np.zeros((nf, _FRAME_OUT_WORDS), np.uint64)
+    for k in range(F):
+        tab[:, k] = ob + np.uint64(k) * row
+    tab[:, MAX_FIELDS] = [o.shape[1] for o in outs]
+    return (lcp_frame_out * nf).from_buffer(tab), tab
 
 
 class lcp_server_params(C.Structure):
@@ -178,18 +227,12 @@ class Plan:
         import torch
         nf = len(frames)
         frames = [f if f.is_contiguous() else f.contiguous() for f in frames]
-        arr = (lcp_frame_in * nf)()
+        for f in frames:
+            assert f.dtype == torch.float32 and f.is_cuda and f.shape[0] == self.F
+        arr, tab = frame_in_table(frames, self.F, methods)
         cap = 0
         bounds = {}
-        # field k of a contiguous (F, n) frame starts k rows after the first
-        # (pointer arithmetic: indexing a tensor per field costs microseconds)
-        for j, f in enumerate(frames):
-            assert f.dtype == torch.float32 and f.is_cuda and f.shape[0] == self.F
-            base, n = f.data_ptr(), f.shape[1]
-            for k in range(self.F):
-                arr[j].fields[k] = base + 4 * n * k
-            arr[j].n = n
-            arr[j].method = METHOD_AUTO if methods is None else methods[j]
+        for n in tab[:, MAX_FIELDS].tolist():
             b = bounds.get(n)
             if b is None:
                 b = bounds[n] = (self.bound(n) + 3) & ~3
@@ -215,23 +258,15 @@ class Plan:
         import torch
         nf = len(offsets) - 1
         offsets = [int(o) for o in offsets]
-        blobs = (lcp_blob * nf)()
-        base = buf.data_ptr()
-        for j in range(nf):
-            blobs[j].data = base + offsets[j]
-            blobs[j].size = (sizes[j] if sizes is not None else offsets[j + 1] - offsets[j])
+        blobs, btab = blob_table(buf.data_ptr(), offsets, sizes)
         if outs is None:
             outs = []
             for j in range(nf):
                 n = self.record_n(buf, offsets[j])
                 outs.append(torch.empty((self.F, n), dtype=torch.float32, device=buf.device))
-        fo = (lcp_frame_out * nf)()
-        for j, o in enumerate(outs):
-            ob, row = o.data_ptr(), 4 * o.stride(0)
+        for o in outs:
             assert o.dtype == torch.float32 and o.stride(1) == 1
-            for k in range(self.F):
-                fo[j].fields[k] = ob + row * k
-            fo[j].capacity = o.shape[1]
+        fo, otab = frame_out_table(outs, self.F)
         n_out = (C.c_uint64 * max(nf, 1))()
         _check(lib().lcp_decompress(self.h, nf, blobs, fo, n_out, _stream_handle()),
                "lcp_decompress")

@@ -39,3 +39,33 @@ def test_status_strings():
     for st in range(9):
         assert L.lcp_status_string(st)
     assert L.lcp_status_string(4) == b"output buffer too small"
+
+
+def test_descriptor_tables_match_field_by_field_filling():
+    """The binding fills its call descriptors as u64 tables; every field must
+    equal what setting the ctypes fields one by one gives (CPU tensors stand in
+    for device ones: only addresses and sizes are read)."""
+    torch = pytest.importorskip("torch")
+    F = 3
+    frames = [torch.empty((F, 1000 + 7 * j)) for j in range(5)]
+    methods = [lcp.METHOD_AUTO, lcp.METHOD_S, lcp.METHOD_T, lcp.METHOD_S, lcp.METHOD_AUTO]
+    arr, _tab = lcp.frame_in_table(frames, F, methods)
+    for j, f in enumerate(frames):
+        assert [arr[j].fields[k] for k in range(F)] == [f[k].data_ptr() for k in range(F)]
+        assert all(not arr[j].fields[k] for k in range(F, lcp.MAX_FIELDS))
+        assert arr[j].n == f.shape[1] and arr[j].method == methods[j]
+    arr, _tab = lcp.frame_in_table(frames[:2], F)
+    assert arr[1].method == lcp.METHOD_AUTO
+    buf = torch.empty(1000, dtype=torch.uint8)
+    offsets = [0, 100, 250, 400, 401, 999]
+    blobs, _b = lcp.blob_table(buf.data_ptr(), offsets)
+    for j in range(5):
+        assert blobs[j].data == buf.data_ptr() + offsets[j]
+        assert blobs[j].size == offsets[j + 1] - offsets[j]
+    blobs, _b = lcp.blob_table(buf.data_ptr(), offsets, sizes=[5, 6, 7, 8, 9])
+    assert [blobs[j].size for j in range(5)] == [5, 6, 7, 8, 9]
+    outs = [torch.empty((F, 2000))[:, : 1500 + j] for j in range(4)]  # row stride 2000
+    fo, _o = lcp.frame_out_table(outs, F)
+    for j, o in enumerate(outs):
+        assert [fo[j].fields[k] for k in range(F)] == [o[k].data_ptr() for k in range(F)]
+        assert fo[j].capacity == o.shape[1]
