@@ -463,7 +463,7 @@ def main():
                      "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
                      "frac": (achieved / HBM_PEAK_GBPS) if achieved else None,
                      "traffic": measured_traffic(args.roofline_kernel),
-                     "timed_launches": klaunch, "timed_every": 8,
+                     "timed_launches": klaunch, "timed_every": 16,
                      "avg_launch_us": (kms / klaunch * 1e3) if klaunch else None,
                      "bytes_per_launch": (kbytes / klaunch) if klaunch else None},
     }

@@ -149,10 +149,11 @@ lcp_status lcp_scratch_bytes(const lcp_params* params, uint64_t* device_bytes);
  * max_batch_frames and max_batch_particles allow: one extent pass, one sort and
  * one set of coding launches per batch (the records are the same bytes as when
  * the frames are compressed one per call).  In multi-frame plans, frames that
- * LCP-FSM codes with LCP-T in a row are enqueued up to eight at a time and their
- * outcomes read back once; a frame whose outcome differs from that prediction
- * is coded again on its own, so the records are again those of one call per
- * frame.  A run only takes frames whose worst-case records fit in out_cap.
+ * LCP-FSM codes with LCP-T in a row are enqueued in runs and their outcomes
+ * read back once per run (a run takes eight frames, twice as many after each
+ * run that commits in full, up to 32); a frame whose outcome differs from that
+ * prediction is coded again on its own, so the records are again those of one
+ * call per frame.  A run only takes frames whose worst-case records fit in out_cap.
  * Errors: LCP_ERR_ARG, LCP_ERR_EB_TOO_SMALL, LCP_ERR_RANGE, LCP_ERR_CAPACITY
  * (out_offsets[n_frames] then holds the bytes required so far), LCP_ERR_DEVICE,
  * LCP_ERR_NO_REFERENCE (LCP_METHOD_T without a resident reference). */
@@ -176,7 +177,7 @@ lcp_status lcp_select(lcp_plan_t plan, int* decision);
 const char* lcp_status_string(lcp_status status);
 
 /* Kernel timing for roofline measurement: while a name is set, one launch in
- * eight of the kernel with that name (the first, the ninth, ...) carries HIP
+ * sixteen of the kernel with that name (the first, the 17th, ...) carries HIP
  * events on its own dispatch; the accumulated time (ms), count and algorithmic
  * bytes of the timed launches are read back with lcp_kernel_timer_read.
  * Sampling keeps the events' cost on the stream (a few microseconds around each

@@ -140,10 +140,9 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* kin,
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kThreads * kScanItems;  // 2048
 
+// Sum of tile blockIdx.x of in[0, nn) into partials[blockIdx.x].
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scan_reduce(const T* in, uint64_t n,
-                                                          const uint32_t* n_dev, T* partials) {
-  uint64_t nn = n_dev ? min((uint64_t)*n_dev, n) : n;
+__device__ inline void scan_reduce_tile(const T* in, uint64_t nn, T* partials) {
   const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
   T s = 0;
 #pragma unroll
@@ -162,14 +161,18 @@ __global__ __launch_bounds__(kThreads) void k_scan_reduce(const T* in, uint64_t 
   }
 }
 
-// Scan of one tile: striped load through LDS, blocked per-thread scan.
 template <typename T>
-__global__ __launch_bounds__(kThreads) void k_scan_apply(T* data, uint64_t n,
-                                                         const uint32_t* n_dev,
-                                                         const T* prefix, int exclusive) {
+__global__ __launch_bounds__(kThreads) void k_scan_reduce(const T* in, uint64_t n,
+                                                          const uint32_t* n_dev, T* partials) {
+  scan_reduce_tile<T>(in, n_dev ? min((uint64_t)*n_dev, n) : n, partials);
+}
+
+// Scan of tile blockIdx.x of data[0, nn), plus prefix[blockIdx.x] when given:
+// striped load through LDS, blocked per-thread scan.
+template <typename T>
+__device__ inline void scan_apply_tile(T* data, uint64_t nn, const T* prefix, int exclusive) {
   __shared__ T tile[kScanTile];
   __shared__ T sm[kThreads / kWave + 1];
-  uint64_t nn = n_dev ? min((uint64_t)*n_dev, n) : n;
   const uint64_t base = (uint64_t)blockIdx.x * kScanTile;
 #pragma unroll
   for (int j = 0; j < kScanItems; j++) {
@@ -203,6 +206,32 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply(T* data, uint64_t n,
     uint64_t i = base + (uint64_t)j * kThreads + threadIdx.x;
     if (i < nn) data[i] = tile[j * kThreads + threadIdx.x];
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kThreads) void k_scan_apply(T* data, uint64_t n,
+                                                         const uint32_t* n_dev,
+                                                         const T* prefix, int exclusive) {
+  scan_apply_tile<T>(data, n_dev ? min((uint64_t)*n_dev, n) : n, prefix, exclusive);
+}
+
+// Up to four u32 arrays of one length scanned side by side, blockIdx.y picking
+// the array (its tile sums at partials + y * tiles): one set of launches
+// rather than one per array.
+struct ScanSet {
+  uint32_t* p[4];
+};
+
+__global__ __launch_bounds__(kThreads) void k_scan_reduce4(ScanSet a, uint64_t n,
+                                                           uint32_t* partials, uint32_t tiles) {
+  scan_reduce_tile<uint32_t>(a.p[blockIdx.y], n, partials + (uint64_t)blockIdx.y * tiles);
+}
+
+__global__ __launch_bounds__(kThreads) void k_scan_apply4(ScanSet a, uint64_t n,
+                                                          const uint32_t* prefix, uint32_t tiles,
+                                                          int exclusive) {
+  scan_apply_tile<uint32_t>(a.p[blockIdx.y], n,
+                            prefix ? prefix + (uint64_t)blockIdx.y * tiles : nullptr, exclusive);
 }
 
 // LCP-T: the frame's codes on the reference grid, in the reference's slot order,
@@ -1022,7 +1051,8 @@ size_t scan_tmp_elems(uint64_t n) {
     m = (m + kScanTile - 1) / kScanTile;
     t += m;
   }
-  return t + 16;
+  // four arrays side by side (scan_device4) need four sets of tile sums
+  return 4 * t + 16;
 }
 
 template <typename T>
@@ -1040,6 +1070,28 @@ void scan_device(T* data, uint64_t n, const uint32_t* n_dev, bool exclusive, T* 
 }
 template void scan_device<uint32_t>(uint32_t*, uint64_t, const uint32_t*, bool, uint32_t*,
                                     hipStream_t);
+
+void scan_device4(uint32_t* const* arrs, int nd, uint64_t n, uint32_t* tmp, hipStream_t s) {
+  if (n == 0 || nd <= 0) return;
+  const uint64_t tiles = (n + kScanTile - 1) / kScanTile;
+  if (nd > 4 || tiles > (uint64_t)kScanTile) {  // tile sums past one tile: one array at a time
+    for (int d = 0; d < nd; d++) scan_device<uint32_t>(arrs[d], n, nullptr, false, tmp, s);
+    return;
+  }
+  ScanSet a;
+  memset(&a, 0, sizeof(a));
+  for (int d = 0; d < nd; d++) a.p[d] = arrs[d];
+  if (tiles == 1) {
+    k_scan_apply4<<<dim3(1, nd), kThreads, 0, s>>>(a, n, nullptr, 0, 0);
+    return;
+  }
+  ScanSet t;
+  memset(&t, 0, sizeof(t));
+  for (int d = 0; d < nd; d++) t.p[d] = tmp + (uint64_t)d * tiles;
+  k_scan_reduce4<<<dim3((uint32_t)tiles, nd), kThreads, 0, s>>>(a, n, tmp, (uint32_t)tiles);
+  k_scan_apply4<<<dim3(1, nd), kThreads, 0, s>>>(t, tiles, nullptr, 0, 1);
+  k_scan_apply4<<<dim3((uint32_t)tiles, nd), kThreads, 0, s>>>(a, n, tmp, (uint32_t)tiles, 0);
+}
 template void scan_device<uint64_t>(uint64_t*, uint64_t, const uint32_t*, bool, uint64_t*,
                                     hipStream_t);
 

@@ -27,7 +27,7 @@ constexpr int kTRunStart = 8;
 // The kernel timer brackets one launch in kTimerStride of the named kernel:
 // each timed launch costs the stream some microseconds on either side (the
 // events' own packets), which a sampled average keeps out of the rest.
-constexpr uint64_t kTimerStride = 8;
+constexpr uint64_t kTimerStride = 16;
 // Temporal frames whose residuals one decode launch keeps as bytes.
 constexpr int kDecSlots = kChainMax;
 
@@ -1235,9 +1235,8 @@ lcp_status decompress_s_batch(lcp_plan_s* P, const ParsedHdr* H, const lcp_blob*
   launch_s_blocks_b(ids, cnt, cum, P->dseg_dev, pre_blk, bb, R, Btot, ntot, P->corner, P->flags,
                     P->err, s);
   uint32_t* tmp32 = reinterpret_cast<uint32_t*>(P->scan_tmp);
-  scan_device<uint32_t>(P->flags, ntot, nullptr, false, tmp32, s);
-  for (int d = 0; d < 3; d++)
-    scan_device<uint32_t>(P->v_slot + (uint64_t)d * ntot, ntot, nullptr, false, tmp32, s);
+  uint32_t* arrs[4] = {P->flags, P->v_slot, P->v_slot + ntot, P->v_slot + 2 * ntot};
+  scan_device4(arrs, 4, ntot, tmp32, s);
   seg_rebase<uint32_t>(P->v_slot, ntot, 3, P->dseg_dev, pre_slot, bs, R, false,
                        reinterpret_cast<uint32_t*>(P->segbase), s);
   launch_s_recon_b(P->flags, P->corner, P->v_slot, P->dseg_dev, pre_slot, bs, R, F, Btot, ntot,
@@ -1431,10 +1430,10 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
         launch_s_blocks(ids, cnt, cum, B, n, total_blocks, h.bn, h.k, P->corner, P->flags,
                         P->err, s);
         uint32_t* tmp32 = reinterpret_cast<uint32_t*>(P->scan_tmp);
-        scan_device<uint32_t>(P->flags, n, nullptr, false, tmp32, s);
-        for (int d = 0; d < 3; d++)
-          scan_device<uint32_t>(reinterpret_cast<uint32_t*>(outs[j].fields[d]), n, nullptr, false,
-                                tmp32, s);
+        uint32_t* arrs[4] = {P->flags, reinterpret_cast<uint32_t*>(outs[j].fields[0]),
+                             reinterpret_cast<uint32_t*>(outs[j].fields[1]),
+                             reinterpret_cast<uint32_t*>(outs[j].fields[2])};
+        scan_device4(arrs, 4, n, tmp32, s);
         launch_s_recon(P->flags, P->corner, B, F, n, h.k, gd, op, q_slot, P->err, s);
       } else {
         const bool extend = chain_len > 0 && chain_len < kChainMax && j > g0 &&

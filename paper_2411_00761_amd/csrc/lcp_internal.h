@@ -208,6 +208,9 @@ int radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, const Seg
 template <typename T>
 void scan_device(T* data, uint64_t n, const uint32_t* n_dev, bool exclusive, T* tmp,
                  hipStream_t s);
+// Inclusive scans of nd <= 4 u32 arrays of length n in one set of launches
+// (tmp: scan_tmp_elems(n) u64 of scratch, as for scan_device).
+void scan_device4(uint32_t* const* arrs, int nd, uint64_t n, uint32_t* tmp, hipStream_t s);
 size_t scan_tmp_elems(uint64_t n);
 // Spatial batch decode.  seg_rebase turns batch-wide inclusive scans of nd
 // arrays (X + d * stride) into per-frame ones (segments by slot or, with
