@@ -231,7 +231,9 @@ void launch_s_recon_b(const uint32_t* blk, const uint32_t* corner, const uint32_
 // The residual symbols of field f are also counted into array f's spread
 // histogram copies (hist_part / hist_max, as launch_encode expects them).
 // Residuals go to v8 as bytes (255: the value is in v_res, written for such
-// values only), or to v_res as u32 when v8 is null.
+// values only), or to v_res as u32 when v8 is null.  zero_words (may be null):
+// the F work records whose Huffman word totals are cleared for the packing
+// that builds its own code.
 void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
                     const uint32_t* perm_ref, const int32_t* q_ref, uint8_t* v8, uint32_t* v_res,
                     int32_t* q_new, uint32_t* err, uint32_t* hist_part,
