@@ -839,6 +839,7 @@ __global__ __launch_bounds__(kThreads) void k_t_recon(const int32_t* q_ref, int 
 // frame's residuals (int32, decoded in place in its output arrays) are added
 // and its float32 values written; only the last frame's codes are stored.
 constexpr int kChainGroup = 8;  // frames of a chain whose residuals load together
+typedef float F4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(kThreads) void k_t_recon_chain(const int32_t* q_ref, int F,
                                                             uint64_t n, GridDev g, ChainOut out,
@@ -864,7 +865,9 @@ __global__ __launch_bounds__(kThreads) void k_t_recon_chain(const int32_t* q_ref
             }
             v[u] = reconstruct(q[u], g.eb_q[f], g.m[f]);
           }
-          reinterpret_cast<float4*>(out.p[j][f])[s4] = make_float4(v[0], v[1], v[2], v[3]);
+          // written once and not read again here: a streaming (non-temporal) store
+          const F4 vv = {v[0], v[1], v[2], v[3]};
+          __builtin_nontemporal_store(vv, reinterpret_cast<F4*>(out.p[j][f]) + s4);
         };
         for (int j0 = 0; j0 < J; j0 += kChainGroup) {
           const int G = min(kChainGroup, J - j0);
