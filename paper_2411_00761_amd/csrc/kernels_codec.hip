@@ -761,12 +761,19 @@ __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* p
 
 // Fallback for arrays whose plain build is too deep (the oracle's loop halves
 // the counts, c -> ceil(c / 2), until the longest code fits): workgroup (a, h)
-// builds with h = blockIdx.y + 1 halvings, all candidates side by side.
+// builds with h = blockIdx.y + h0 halvings, candidates side by side.
+// A launch builds the candidates from h0 halvings on; one from h0 > 1 skips
+// the arrays for which fewer halvings already fit (the pick below never reads
+// past the first count that fits, so those entries need not be written).
+constexpr int kFirstHalvings = 4;  // candidates built first; the rest only when none fits
+
 __global__ __launch_bounds__(kHT) void k_huff_lengths(const ArrWork* W, uint8_t* lens_all,
-                                                      uint32_t* maxd_all) {
+                                                      uint32_t* maxd_all, int h0) {
   __shared__ uint64_t sm64[8192];
-  const int a = blockIdx.x, halvings = blockIdx.y + 1;
+  const int a = blockIdx.x, halvings = blockIdx.y + h0;
   if (maxd_all[(uint64_t)a * kHalvings] <= (uint32_t)kMaxLen) return;
+  for (int h = 1; h < h0; h++)
+    if (maxd_all[(uint64_t)a * kHalvings + h] <= (uint32_t)kMaxLen) return;
   const ArrWork& w = W[a];
   const int t = threadIdx.x;
   const int nsym = sym_bound(w.maxv) + 1;
@@ -2526,7 +2533,9 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
     launch_timed("huff_build", 0, k_huff_build, NA, kHT, 0, s, L.arrs, X.hist_part, X.hist_max,
                  work, X.huff_lens, X.huff_maxd, hist_done ? 1 : 0, chunk_log2);
   if (!hist_done) {
-    k_huff_lengths<<<dim3(NA, kHalvings - 1), kHT, 0, s>>>(work, X.huff_lens, X.huff_maxd);
+    k_huff_lengths<<<dim3(NA, kFirstHalvings), kHT, 0, s>>>(work, X.huff_lens, X.huff_maxd, 1);
+    k_huff_lengths<<<dim3(NA, kHalvings - 1 - kFirstHalvings), kHT, 0, s>>>(
+        work, X.huff_lens, X.huff_maxd, 1 + kFirstHalvings);
     k_huff_codes<<<NA, kHT, 0, s>>>(L.arrs, work, X.huff_lens, X.huff_maxd, chunk_log2);
   }
   const uint32_t slot32 = enc_slot_words(false, chunk_log2), slot64 = enc_slot_words(true, chunk_log2);
