@@ -765,7 +765,7 @@ __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* p
 // A launch builds the candidates from h0 halvings on; one from h0 > 1 skips
 // the arrays for which fewer halvings already fit (the pick below never reads
 // past the first count that fits, so those entries need not be written).
-constexpr int kFirstHalvings = 4;  // candidates built first; the rest only when none fits
+constexpr int kFirstHalvings = 8;  // candidates built first; the rest only when none fits
 
 __global__ __launch_bounds__(kHT) void k_huff_lengths(const ArrWork* W, uint8_t* lens_all,
                                                       uint32_t* maxd_all, int h0) {
