@@ -109,9 +109,11 @@ typedef struct {
   uint64_t capacity;
 } lcp_frame_out;
 
-/* Create a plan: validates params, allocates all device scratch and the resident
- * stream state on params->device, and, when block_log2 == -1, runs the
- * block-size search on a stride sample of the given frame (sample_fields: device
+/* Create a plan (the parameters theta of the compressor, Sec. 4; the block size
+ * p = 2^k of Sec. 6.2.1 and its search, Sec. 7.4.1): validates params, allocates
+ * all device scratch and the resident stream state on params->device, and, when
+ * block_log2 == -1, runs the block-size search on a stride sample of the given
+ * frame (sample_fields: device
  * pointers, n_fields of them, sample_n values each; the stride is
  * max(1, sample_n >> 20)).  The plan is returned in *out.
  * Errors: LCP_ERR_ARG, LCP_ERR_BUDGET, LCP_ERR_DEVICE, and the search's errors. */
@@ -137,7 +139,13 @@ uint64_t lcp_bound(lcp_plan_t plan, uint64_t n);
  * of its arena).  Errors: LCP_ERR_ARG. */
 lcp_status lcp_scratch_bytes(const lcp_params* params, uint64_t* device_bytes);
 
-/* Compress n_frames frames, in stream order, into out (device, out_cap bytes).
+/* Compress n_frames frames, in stream order, into out (device, out_cap bytes):
+ * the compression f of Sec. 4, Eq. 1-2 (|d - d'| <= eb pointwise).  A spatial
+ * frame is LCP-S (Sec. 6: Eq. 5 quantisation, Eq. 6 blocks, Sec. 6.2.2 delta and
+ * Huffman / fixed coding); a temporal frame is LCP-T (Sec. 7.1) against the
+ * reference Alg. 1 names (Sec. 7.3), the choice made by LCP-FSM (Sec. 7.2).
+ * Arguments: frames[j].fields are device SoA float32 arrays owned by the caller,
+ * read only; out is a caller-owned device buffer, 4-byte aligned.
  * Record j is written at out + out_offsets[j] and occupies
  * out_offsets[j+1] - out_offsets[j] bytes (out_offsets: host array of
  * n_frames + 1 entries; records are 4-byte aligned and back to back).
@@ -161,7 +169,12 @@ lcp_status lcp_compress(lcp_plan_t plan, uint64_t n_frames, const lcp_frame_in* 
                         void* out, uint64_t out_cap, uint64_t* out_offsets,
                         int* methods_used, uint32_t* const* perms, hipStream_t stream);
 
-/* Decompress n_frames records, in stream order.  Frame j's float32 values are
+/* Decompress n_frames records, in stream order: the decompression g of Sec. 4
+ * (x' = (2q + 1) eb + min, Eq. 5), with the block structure of Sec. 6.2.1
+ * expanded and a temporal record added to its reference (Sec. 7.1), which must
+ * have been decoded before it by this plan (recursive retrieval, Sec. 7.3).
+ * blobs[j].data: caller-owned device records, 4-byte aligned, read only; outs:
+ * caller-owned device arrays.  Frame j's float32 values are
  * written, in slot order, to outs[j].fields[f][0..n); n_out (host) receives n.
  * A temporal record needs its reference (the previous frame, or the last anchor
  * for the first frame of a batch) decoded earlier by this plan.
@@ -170,7 +183,8 @@ lcp_status lcp_compress(lcp_plan_t plan, uint64_t n_frames, const lcp_frame_in* 
 lcp_status lcp_decompress(lcp_plan_t plan, uint64_t n_frames, const lcp_blob* blobs,
                           const lcp_frame_out* outs, uint64_t* n_out, hipStream_t stream);
 
-/* What LCP-FSM decides for the next frame compressed with LCP_METHOD_AUTO:
+/* LCP-FSM (Sec. 7.2) with Alg. 1's reference rule (Sec. 7.3): what the next
+ * frame compressed with LCP_METHOD_AUTO gets:
  * LCP_DECIDE_S, LCP_DECIDE_T or LCP_DECIDE_COMPARE (run both, keep the smaller). */
 lcp_status lcp_select(lcp_plan_t plan, int* decision);
 
@@ -220,6 +234,11 @@ typedef struct {
   uint64_t out_cap;    /* compress: bytes available at out */
   lcp_blob blob;       /* decompress: the stream's next record (decode order = stream order) */
   lcp_frame_out dst;   /* decompress: where the frame goes */
+  hipStream_t after;   /* the caller's stream (NULL: the null stream) that produces
+                          the request's inputs and last used its outputs:
+                          lcp_server_submit records an event on it, and the
+                          request's work starts only after what was enqueued there
+                          before the submit */
 } lcp_request;
 
 typedef struct {

@@ -140,6 +140,7 @@ int lco_make_grid(float lo, float hi, double eb_f, lco_grid* g) {
   if (!isfinite(lo) || !isfinite(hi) || !(eb_f > 0) || !isfinite(eb_f)) return LCO_ERR_ARG;
   double a = fabs((double)lo), b = fabs((double)hi);
   double M = (a > b ? a : b) + 2.0 * eb_f;
+  if (!isfinite(M)) return LCO_ERR_RANGE; /* the bound overflows the double range */
   int E;
   frexp(M, &E); /* M < 2^E */
   if (E < -100) E = -100;

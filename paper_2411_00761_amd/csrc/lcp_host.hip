@@ -38,25 +38,44 @@ struct HostGrid {
   int E;
 };
 
-// Eq. 5 with a float32 output: the exact bin centre is within eb_q of x and the
-// float32 rounding of the centre adds at most half an ulp of the top binade
-// 2^E, where |x| + 2 eb < 2^E; eb_q = eb - 2^(E-24), rounded down to float,
-// keeps every reconstruction within eb.
+// Eq. 5 with a float32 output.  Every reconstruction of the field lies below
+// 2^E in magnitude, where 2^E is the first power of two above the double sum
+// top = max(|lo|, |hi|) + 2 eb (E at least -100).  Rounding an exact bin centre
+// to float32 there costs at most half an ulp of the binade [2^(E-1), 2^E),
+// i.e. 2^(E-24), so the half bin width eb_q is the largest float32 not above
+// eb - 2^(E-24); a bound below two such half ulps is refused.  The exponents
+// and the rounding toward zero are read off the IEEE-754 bit fields.
 lcp_status make_grid(float lo, float hi, double eb, HostGrid* g) {
   if (!isfinite(lo) || !isfinite(hi) || !(eb > 0) || !isfinite(eb)) return LCP_ERR_ARG;
-  double M = fmax(fabs((double)lo), fabs((double)hi)) + 2.0 * eb;
-  int E;
-  frexp(M, &E);
+  const double alo = lo < 0 ? -(double)lo : (double)lo;
+  const double ahi = hi < 0 ? -(double)hi : (double)hi;
+  const double top = (alo > ahi ? alo : ahi) + 2.0 * eb;
+  uint64_t tb;
+  memcpy(&tb, &top, 8);
+  const int top_biased = (int)((tb >> 52) & 0x7FF);
+  if (top_biased == 0x7FF) return LCP_ERR_RANGE;  // the bound overflows the double range
+  // top = 1.f x 2^(biased - 1023) < 2^(biased - 1022); a subnormal or zero top
+  // is far below the floor of -100
+  int E = top_biased == 0 ? -100 : top_biased - 1022;
   if (E < -100) E = -100;
-  double delta = ldexp(1.0, E - 24);
-  if (!(eb >= 2.0 * delta)) return LCP_ERR_EB_TOO_SMALL;
-  double t = eb - delta;
-  float e = (float)t;
-  if ((double)e > t) e = nextafterf(e, 0.0f);
-  if (!(e > 0.0f)) return LCP_ERR_EB_TOO_SMALL;
+  uint64_t db = (uint64_t)(E - 24 + 1023) << 52;  // 2^(E-24), a normal double here
+  double half_ulp;
+  memcpy(&half_ulp, &db, 8);
+  if (eb < half_ulp * 2) return LCP_ERR_EB_TOO_SMALL;
+  // exact: half_ulp is a power of two no larger than eb / 2
+  const double t = eb - half_ulp;
+  uint64_t u;
+  memcpy(&u, &t, 8);
+  const int te = (int)((u >> 52) & 0x7FF) - 1023;  // t in [2^te, 2^(te+1))
+  uint32_t fb;
+  if (te > 127) fb = 0x7F7FFFFFu;  // above every float32: the largest one
+  else if (te < -126) return LCP_ERR_EB_TOO_SMALL;
+  else fb = ((uint32_t)(te + 127) << 23) | (uint32_t)((u >> 29) & 0x7FFFFFu);  // truncate
+  float e;
+  memcpy(&e, &fb, 4);
   g->m = lo;
   g->eb_q = e;
-  g->inv = 1.0 / (2.0 * (double)e);
+  g->inv = 0.5 / (double)e;  // 2 e is exact, so this is the rounding of 1 / (2 e)
   g->eb = eb;
   g->E = E;
   return LCP_OK;
@@ -97,6 +116,10 @@ struct lcp_plan_s {
   void* own_dev = nullptr;   // owned device scratch block
   void* own_host = nullptr;  // owned pinned host block
   void* state_dev = nullptr; // reference codes and permutations
+  // the scratch pointers below address live memory: set by bind_scratch,
+  // cleared when a server takes the memory back (or the search's temporary
+  // scratch is freed); compress and decompress refuse to run without it
+  bool bound = false;
   size_t scratch_bytes = 0, host_bytes = 0, state_bytes = 0;
 
   // scratch (batch-wide arrays hold NB slots)
@@ -162,8 +185,8 @@ struct lcp_plan_s {
   double eb_f[kMaxF];
   uint64_t seq = 0;
   // LCP-FSM
-  bool fsm_t = false;
-  int interval = 1, countdown = 0;
+  uint8_t fsm_state = 0;  // S1X (see the LCP-FSM table)
+  int untested = 0;
   uint64_t last_s = 0;
   bool have_last_s = false;
 
@@ -748,8 +771,18 @@ lcp_status compress_t(lcp_plan_s* P, const float* const* x, uint64_t n, const Re
 }
 
 // ------------------------------------------------------------------ LCP-FSM
-// S state with a test interval (S1X, S2X, ... S16X) and a countdown of frames
-// coded with S untested; T state.  A frame with no reference counts as an S win.
+// Sec. 7.2 as a transition table.  States: S1X, S2X, S4X, S8X, S16X (LCP-S,
+// with a comparison of both methods on every 1st, 2nd, ... 16th frame) and T
+// (LCP-T, its size checked against the last LCP-S record).  `untested` counts
+// the S frames still to go before the next comparison.  The size of a frame's
+// outcome picks the event; the event picks the next state:
+//   no reference (the stream's first frame, or a batch start without anchor):
+//     coded with S and taken as a won comparison;
+//   an S state's untested frame;
+//   a comparison won by S (ties go to S) or by T;
+//   a T frame no larger than the last S record (kept), or larger (S is run as
+//     well and the smaller kept: either way the machine leaves T for S1X when
+//     S wins, and stays in T when T is still the smaller).
 bool first_in_batch(const lcp_plan_s* P, uint64_t seq) {
   return P->p.batch_size == 0 ? seq == 0 : seq % (uint64_t)P->p.batch_size == 0;
 }
@@ -761,34 +794,40 @@ const RefState* reference_for(const lcp_plan_s* P, uint64_t n) {
   return r;
 }
 
+enum : uint8_t { kFsmS1, kFsmS2, kFsmS4, kFsmS8, kFsmS16, kFsmT, kFsmStates };
+enum : uint8_t { kEvNoRef, kEvUntested, kEvCmpS, kEvCmpT, kEvTKept, kEvTLost, kFsmEvents };
+constexpr uint8_t kFsmNone = 0xFF;  // an event the state cannot see
+constexpr uint8_t kFsmNext[kFsmStates][kFsmEvents] = {
+    //        no ref  untested  cmp S    cmp T   T kept    T lost
+    /* S1  */ {kFsmS2, kFsmS1, kFsmS2, kFsmT, kFsmNone, kFsmNone},
+    /* S2  */ {kFsmS4, kFsmS2, kFsmS4, kFsmT, kFsmNone, kFsmNone},
+    /* S4  */ {kFsmS8, kFsmS4, kFsmS8, kFsmT, kFsmNone, kFsmNone},
+    /* S8  */ {kFsmS16, kFsmS8, kFsmS16, kFsmT, kFsmNone, kFsmNone},
+    /* S16 */ {kFsmS16, kFsmS16, kFsmS16, kFsmT, kFsmNone, kFsmNone},
+    /* T   */ {kFsmS2, kFsmNone, kFsmNone, kFsmNone, kFsmT, kFsmS1},
+};
+// Frames between comparisons in each S state, once entered by an S win.
+constexpr int kFsmGap[kFsmStates] = {0, 1, 3, 7, 15, 0};
+
 int fsm_decide(const lcp_plan_s* P, bool have_ref) {
   if (!P->p.multi_frame || !have_ref) return LCP_DECIDE_S;
-  if (P->fsm_t) return LCP_DECIDE_T;
-  return P->countdown > 0 ? LCP_DECIDE_S : LCP_DECIDE_COMPARE;
+  if (P->fsm_state == kFsmT) return LCP_DECIDE_T;
+  return P->untested > 0 ? LCP_DECIDE_S : LCP_DECIDE_COMPARE;
 }
 
-void fsm_s_win(lcp_plan_s* P) {
-  P->interval = P->interval * 2 > 16 ? 16 : P->interval * 2;
-  P->countdown = P->interval - 1;
-}
-
+// One frame's outcome: what was decided, whether a reference existed, and
+// which method's record was kept.
 void fsm_update(lcp_plan_s* P, int decision, bool have_ref, bool chose_t) {
-  if (!have_ref) {
-    if (P->fsm_t) {
-      P->fsm_t = false;
-      P->interval = 1;
-    }
-    fsm_s_win(P);
-  } else if (decision == LCP_DECIDE_S) {
-    P->countdown--;
-  } else if (decision == LCP_DECIDE_COMPARE) {
-    if (chose_t) P->fsm_t = true;
-    else fsm_s_win(P);
-  } else if (!chose_t) {
-    P->fsm_t = false;
-    P->interval = 1;
-    P->countdown = 0;
-  }
+  uint8_t ev;
+  if (!have_ref) ev = kEvNoRef;
+  else if (decision == LCP_DECIDE_S) ev = kEvUntested;
+  else if (decision == LCP_DECIDE_COMPARE) ev = chose_t ? kEvCmpT : kEvCmpS;
+  else ev = chose_t ? kEvTKept : kEvTLost;
+  const uint8_t next = kFsmNext[P->fsm_state][ev];
+  if (next == kFsmNone) return;  // not reachable: decisions follow the state
+  if (ev == kEvUntested) P->untested--;
+  else if (next != kFsmT) P->untested = ev == kEvTLost ? 0 : kFsmGap[next];
+  P->fsm_state = next;
 }
 
 int free_q(const lcp_plan_s* P, int avoid) {
@@ -958,7 +997,7 @@ int plan_run(const lcp_plan_s* P, const lcp_frame_in* fr, uint64_t nf, uint64_t 
     bool ok = true;
     for (int k = 0; k < P->F; k++) ok = ok && f.fields[k] != nullptr;
     if (!ok) break;
-    if (f.method == LCP_METHOD_S || (f.method == LCP_METHOD_AUTO && !P->fsm_t)) break;
+    if (f.method == LCP_METHOD_S || (f.method == LCP_METHOD_AUTO && P->fsm_state != kFsmT)) break;
     const bool first = P->p.batch_size == 0 ? seq == 0 : seq % (uint64_t)P->p.batch_size == 0;
     const RefState& ref = first ? P->anchor : prev;
     if (!ref.valid || ref.n != f.n) break;
@@ -1613,6 +1652,7 @@ void bind_scratch(lcp_plan_s* P, void* dev, void* host, hipStream_t s) {
   launch_fill_u32(reinterpret_cast<uint32_t*>(P->hist_max), 2 * P->hist_copies, 0u, s);
   launch_fill_u32(P->err, 1, 0u, s);
   P->err_clean = true;
+  P->bound = true;
 }
 
 lcp_status alloc_state(lcp_plan_s* P) {
@@ -1810,6 +1850,7 @@ lcp_status plan_create_unbound(const lcp_params* params, const float* const* sam
     }
     if (dev) (void)hipFree(dev);
     if (host) (void)hipHostFree(host);
+    P->bound = false;
   }
   if (st) {
     free_plan(P);
@@ -1823,6 +1864,7 @@ size_t plan_scratch_bytes(lcp_plan_t P) { return P->scratch_bytes; }
 size_t plan_host_bytes(lcp_plan_t P) { return P->host_bytes; }
 size_t plan_state_bytes(lcp_plan_t P) { return P->state_bytes; }
 void plan_bind(lcp_plan_t P, void* dev, void* host, hipStream_t s) { bind_scratch(P, dev, host, s); }
+void plan_unbind(lcp_plan_t P) { P->bound = false; }
 
 }  // namespace lcp
 
@@ -1877,9 +1919,8 @@ lcp_status lcp_plan_reset(lcp_plan_t plan) {
   plan->danchor = RefState();
   plan->have_eb = false;
   plan->seq = 0;
-  plan->fsm_t = false;
-  plan->interval = 1;
-  plan->countdown = 0;
+  plan->fsm_state = kFsmS1;
+  plan->untested = 0;
   plan->last_s = 0;
   plan->have_last_s = false;
   return LCP_OK;
@@ -1907,7 +1948,7 @@ lcp_status lcp_compress(lcp_plan_t plan, uint64_t n_frames, const lcp_frame_in* 
                         void* out, uint64_t out_cap, uint64_t* out_offsets, int* methods_used,
                         uint32_t* const* perms, hipStream_t stream) {
   if (!plan || (!frames && n_frames) || !out_offsets || (!out && n_frames)) return LCP_ERR_ARG;
-  if ((uintptr_t)out & 3) return LCP_ERR_ARG;
+  if ((uintptr_t)out & 3 || !plan->bound) return LCP_ERR_ARG;
   TimerScope ts(plan);
   uint8_t* o = reinterpret_cast<uint8_t*>(out);
   uint64_t off = 0;
@@ -1989,7 +2030,7 @@ lcp_status lcp_compress(lcp_plan_t plan, uint64_t n_frames, const lcp_frame_in* 
 
 lcp_status lcp_decompress(lcp_plan_t plan, uint64_t n_frames, const lcp_blob* blobs,
                           const lcp_frame_out* outs, uint64_t* n_out, hipStream_t stream) {
-  if (!plan || (n_frames && (!blobs || !outs || !n_out))) return LCP_ERR_ARG;
+  if (!plan || (n_frames && (!blobs || !outs || !n_out)) || !plan->bound) return LCP_ERR_ARG;
   TimerScope ts(plan);
   for (uint64_t j = 0; j < n_frames; j += kMaxBatchFrames) {
     uint64_t g = n_frames - j < (uint64_t)kMaxBatchFrames ? n_frames - j : kMaxBatchFrames;

@@ -169,6 +169,9 @@ size_t plan_scratch_bytes(lcp_plan_s* P);
 size_t plan_host_bytes(lcp_plan_s* P);
 size_t plan_state_bytes(lcp_plan_s* P);
 void plan_bind(lcp_plan_s* P, void* dev, void* host, hipStream_t s);
+// Marks the plan's scratch as gone (its memory returned to the server's arena):
+// compress and decompress then fail with LCP_ERR_ARG until the next plan_bind.
+void plan_unbind(lcp_plan_s* P);
 
 // ---- kernels_core.hip ----
 // Spatial batch front end.  pre_* are device prefix tables (R + 1 entries) of

@@ -41,6 +41,10 @@ struct ServedStream {
 struct Ticket {
   lcp_request req;
   lcp_result res;
+  // recorded on req.after at submit: the worker's stream waits for it, so the
+  // request reads inputs and overwrites outputs only after the caller's
+  // earlier work on them
+  hipEvent_t ready = nullptr;
   bool done = false;
 };
 
@@ -162,9 +166,16 @@ void worker_main(lcp_server_s* S) {
       plan = S->streams[t->req.stream].plan;
       t->res.t_start_ns = now_ns();
     }
-    plan_bind(plan, static_cast<uint8_t*>(S->arena_mem) + off, host, hs);
     lcp_result res = t->res;
-    run_request(plan, t->req, hs, &res);
+    if (t->ready && hipStreamWaitEvent(hs, t->ready, 0) != hipSuccess) {
+      res.status = LCP_ERR_DEVICE;
+    } else {
+      plan_bind(plan, static_cast<uint8_t*>(S->arena_mem) + off, host, hs);
+      run_request(plan, t->req, hs, &res);
+      plan_unbind(plan);
+    }
+    if (t->ready) (void)hipEventDestroy(t->ready);
+    t->ready = nullptr;
     res.t_end_ns = now_ns();
     {
       std::lock_guard<std::mutex> lk(S->mu);
@@ -265,12 +276,23 @@ lcp_status lcp_server_open_stream(lcp_server_t S, const lcp_params* params,
 lcp_status lcp_server_submit(lcp_server_t S, const lcp_request* req, uint64_t* ticket) {
   if (!S || !req || !ticket) return LCP_ERR_ARG;
   if (req->kind != LCP_REQ_COMPRESS && req->kind != LCP_REQ_DECOMPRESS) return LCP_ERR_ARG;
+  hipEvent_t ready = nullptr;
+  if (hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess) return LCP_ERR_DEVICE;
+  if (hipEventRecord(ready, req->after) != hipSuccess) {
+    (void)hipEventDestroy(ready);
+    return LCP_ERR_DEVICE;
+  }
   std::lock_guard<std::mutex> lk(S->mu);
-  if (S->worker_error) return S->worker_error;
-  if (req->stream < 0 || req->stream >= (int)S->streams.size()) return LCP_ERR_ARG;
+  lcp_status bad = S->worker_error;
+  if (!bad && (req->stream < 0 || req->stream >= (int)S->streams.size())) bad = LCP_ERR_ARG;
+  if (bad) {
+    if (ready) (void)hipEventDestroy(ready);
+    return bad;
+  }
   const uint64_t id = S->next_ticket++;
   Ticket& t = S->tickets[id];
   t.req = *req;
+  t.ready = ready;
   memset(&t.res, 0, sizeof(t.res));
   t.res.t_submit_ns = now_ns();
   S->pending.push_back(id);

@@ -112,7 +112,7 @@ class lcp_server_params(C.Structure):
 class lcp_request(C.Structure):
     _fields_ = [("kind", C.c_int), ("stream", C.c_int), ("frame", lcp_frame_in),
                 ("out", C.c_void_p), ("out_cap", C.c_uint64), ("blob", lcp_blob),
-                ("dst", lcp_frame_out)]
+                ("dst", lcp_frame_out), ("after", C.c_void_p)]
 
 
 class lcp_result(C.Structure):
@@ -345,6 +345,9 @@ class Server:
         return sid.value
 
     def _submit(self, rq, keep) -> int:
+        import torch
+        # the request waits for the work torch has queued on the buffers so far
+        rq.after = torch.cuda.current_stream(self.device).cuda_stream
         t = C.c_uint64()
         _check(lib().lcp_server_submit(self.h, C.byref(rq), C.byref(t)), "lcp_server_submit")
         self._keep[t.value] = keep

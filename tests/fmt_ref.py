@@ -159,3 +159,82 @@ def t_codes(rec: bytes, ref_q):
     assert P["mode"] == 1
     return [[int(ref_q[f][s]) + unzigzag(P["arrays"][f][s]) for s in range(P["n"])]
             for f in range(P["F"])], P
+
+
+# ------------------------------------------------------------------ coder cost
+# The writer side of the array coding, for pins of the coder choice: symbols of
+# values (values below 4096 are symbols themselves; a larger value is a length
+# class followed by its bits below the leading one), length-limited Huffman
+# lengths under the stated tie rules, and the exact byte cost of both coders.
+def symbol(v: int) -> tuple[int, int]:
+    """(symbol, raw bits after its code)."""
+    if v < DIRECT:
+        return v, 0
+    b = v.bit_length()
+    return DIRECT + b - FIRST_CLASS_BITS, b - 1
+
+
+def huffman_lengths(counts: dict[int, int], limit: int = MAX_LEN) -> tuple[dict[int, int], int]:
+    """symbol -> code length, and the number of halvings it took.  Leaves in
+    (count, symbol) order; internal nodes queue in creation order; a merge takes
+    the lighter head twice, the leaf when the two heads weigh the same."""
+    cnt = {s: c for s, c in counts.items() if c > 0}
+    halvings = 0
+    while True:
+        leaves = sorted(cnt, key=lambda s: (cnt[s], s))
+        if len(leaves) == 1:
+            return {leaves[0]: 1}, halvings
+        weight = [cnt[s] for s in leaves]
+        kids: list[tuple[int, int]] = []
+        li, ii = 0, 0  # heads of the leaf queue and of the internal queue
+        for _ in range(len(leaves) - 1):
+            pair = []
+            for _ in range(2):
+                leaf_ok = li < len(leaves)
+                int_ok = ii < len(kids)
+                if leaf_ok and (not int_ok or weight[li] <= weight[len(leaves) + ii]):
+                    pair.append(li)
+                    li += 1
+                else:
+                    pair.append(len(leaves) + ii)
+                    ii += 1
+            weight.append(weight[pair[0]] + weight[pair[1]])
+            kids.append((pair[0], pair[1]))
+        depth = [0] * len(weight)
+        for j in range(len(kids) - 1, -1, -1):  # root last: walk down from it
+            node = len(leaves) + j
+            for c in kids[j]:
+                depth[c] = depth[node] + 1
+        lengths = {leaves[i]: depth[i] for i in range(len(leaves))}
+        if max(lengths.values()) <= limit:
+            return lengths, halvings
+        cnt = {s: (c + 1) // 2 for s, c in cnt.items()}
+        halvings += 1
+
+
+def coder_costs(values, chunk_log2: int) -> tuple[int, int, dict[int, int]]:
+    """(fixed bytes, Huffman bytes, Huffman lengths) of one array: fixed =
+    4 ceil(n w / 32) with w the bit width of the largest value; Huffman = 4 per
+    table entry + 4 per chunk offset + 4 per payload word, each chunk of
+    2^chunk_log2 values starting on a fresh word."""
+    vals = [int(v) for v in values]
+    n = len(vals)
+    w = max(vals).bit_length() if n else 0
+    fixed = 4 * ((n * w + 31) // 32)
+    if n == 0:
+        return fixed, 0, {}
+    counts: dict[int, int] = {}
+    for v in vals:
+        s, _ = symbol(v)
+        counts[s] = counts.get(s, 0) + 1
+    lengths, _ = huffman_lengths(counts)
+    C = 1 << chunk_log2
+    words = 0
+    for c0 in range(0, n, C):
+        bits = 0
+        for v in vals[c0:c0 + C]:
+            s, e = symbol(v)
+            bits += lengths[s] + e
+        words += (bits + 31) // 32
+    nchunks = (n + C - 1) // C
+    return fixed, 4 * len(lengths) + 4 * nchunks + 4 * words, lengths
