@@ -1,14 +1,22 @@
 """Throughput benchmark of the LCP hot path on one MI355X.
 
-Default workload: the MD-like trajectory, 64 frames of 4,194,304 particles on a
-256x128x128 jittered lattice (spacing 1.0, jitter sigma 0.1, per-step Gaussian
-displacement sigma 0.01), float32 xyz, eb = 1e-4 x value range of the first
-frame, Alg. 1 batches of 16 frames with LCP-FSM choosing S or T per frame.
+Default workload (the headline value): the MD-like trajectory, 64 frames of
+4,194,304 particles on a 256x128x128 jittered lattice (spacing 1.0, jitter sigma
+0.1, per-step Gaussian displacement sigma 0.01), float32 xyz, eb = 1e-4 x value
+range of the first frame, Alg. 1 batches of 16 frames with LCP-FSM choosing S
+or T per frame.  One step = compress the 64 frames (one multi-frame stream) +
+decompress them (a second plan replays the stream).  The inputs are resident in
+HBM before the timed region.  Throughput follows Eq. 4: size(D) / time,
+size(D) = 4 * F * n bytes per frame.
 
-One step = compress the 64 frames (one multi-frame stream) + decompress them
-(a second plan replays the stream).  The inputs are resident in HBM before the
-timed region.  Throughput follows Eq. 4: size(D) / time, size(D) = 4 * 3 * n
-bytes per frame.  Prints one JSON line.
+Further legs (extra keys of the one JSON line): the uniform frame (2^18
+particles, eb 1e-3, LCP-S only), the cosmology-like snapshot (2^27 particles x 6
+fields, eb 1e-4 x range per field, LCP-S only), the batched form (256
+independent frames per call) and the served form (32 streams).  Each leg reports
+its whole-path fraction of the HBM roofline in algorithmic bytes:
+  S compress 4FN + C, S decompress C + 4FN,
+  T compress 4FN (frame) + 4FN (reference codes) + 4N (permutation) + C + 4FN
+  (new reference codes), T decompress C + 4FN + 4FN + 4FN.
 """
 from __future__ import annotations
 
@@ -28,15 +36,62 @@ sys.path.insert(0, ROOT)
 METRIC = "compress/decompress GB/s at fixed eb + ratio; batched/served vs plain, p99"
 HBM_PEAK_GBPS = 8000.0
 
-# Algorithmic bytes per particle of the kernel the roofline is quoted on (see
-# DESIGN.md "Roofline accounting"): the temporal residual kernel reads the
-# frame (12 B), the reference codes (12 B) and the slot permutation (4 B), and
-# writes the residual symbols (12 B) and the new codes (12 B).
+# The roofline is quoted on the dominant kernel of the headline step, the
+# temporal residual kernel; its algorithmic bytes per particle are its share of
+# LCP-T compression's: the frame (12 B), the reference codes (12 B) and the slot
+# permutation (4 B) read, the new reference codes (12 B) written.
 ROOFLINE_KERNEL = "t_resid"
+
+MALL_NOTE = ("the 256 MB Infinity Cache (MALL) holds a 4,194,304-particle frame's reference "
+             "codes (48 MiB) and permutation (16 MiB), written by the previous launch, so part "
+             "of this 'HBM' traffic is served from it")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def s_bytes(F, n, c):
+    """Algorithmic bytes of one spatial frame (compress = decompress = 4FN + C)."""
+    return 4 * F * n + c
+
+
+def t_bytes_c(F, n, c):
+    return 12 * F * n + 4 * n + c
+
+
+def t_bytes_d(F, n, c):
+    return 12 * F * n + c
+
+
+def path_frac(byts, seconds):
+    gbps = byts / seconds / 1e9
+    return {"algorithmic_bytes": int(byts), "seconds": seconds, "achieved_GBps": gbps,
+            "peak_GBps": HBM_PEAK_GBPS, "frac": gbps / HBM_PEAK_GBPS}
+
+
+def copy_ceiling(torch, dev, mib=2048, reps=5):
+    """What a plain device copy and a plain read sustain on this GPU: torch's copy
+    kernel over `mib` MiB (read + write counted) and a sum over the same buffer
+    (read only), best of `reps`, timed with events on the current stream."""
+    src = torch.ones(mib << 18, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    nbytes = src.numel() * 4
+    best_c = best_r = 1e9
+    for _ in range(reps):
+        a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        a.record()
+        dst.copy_(src)
+        b.record()
+        src.sum()
+        c.record()
+        c.synchronize()
+        best_c = min(best_c, a.elapsed_time(b) * 1e-3)
+        best_r = min(best_r, b.elapsed_time(c) * 1e-3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return {"copy_GBps": 2 * nbytes / best_c / 1e9, "read_GBps": nbytes / best_r / 1e9,
+            "buffer_MiB": mib, "how": "torch copy_ and sum over a device buffer, best of %d" % reps}
 
 
 def cpu_model() -> str:
@@ -50,26 +105,119 @@ def cpu_model() -> str:
     return platform.processor()
 
 
-def cpu_baseline(frames_np, eb_rel, batch, k, n_frames):
-    """The CPU oracle (single thread) on the first n_frames frames of the workload."""
+def cpu_baseline(frames_np, eb_rel, batch, k, gpu_methods, n_bytes_frame):
+    """The CPU oracle (one thread) on the first frames of the workload, timed per
+    spatial and per temporal frame, then weighted by the methods the GPU stream
+    used on all its frames, so that the figure has the same S/T mix."""
     import oracle as O
     st = O.Stream(O.EB_REL_GLOBAL, eb_rel, batch_size=batch, block_log2=k,
                   max_n=frames_np[0].shape[1])
     dec = O.Stream(O.EB_REL_GLOBAL, eb_rel, batch_size=batch, block_log2=k,
                    max_n=frames_np[0].shape[1])
-    t0 = time.perf_counter()
-    recs = [st.compress(frames_np[j])[0] for j in range(n_frames)]
-    t1 = time.perf_counter()
-    for r in recs:
-        dec.decompress(r)
-    t2 = time.perf_counter()
-    nbytes = sum(frames_np[j].nbytes for j in range(n_frames))
-    return dict(value=nbytes / (t2 - t0) / 1e9, unit="GB/s", cores=1, kind="oracle",
-                sample=f"first {n_frames} frames of the workload at full n, compress+decompress "
-                       f"(compress {nbytes / (t1 - t0) / 1e9:.4f} GB/s, decompress "
-                       f"{nbytes / (t2 - t1) / 1e9:.4f} GB/s), host CPU: {cpu_model()}, "
-                       f"nproc {os.cpu_count()}",
-                compress_s=t1 - t0, decompress_s=t2 - t1)
+    tc = {O.METHOD_S: [], O.METHOD_T: []}
+    td = {O.METHOD_S: [], O.METHOD_T: []}
+    for x in frames_np:
+        t0 = time.perf_counter()
+        rec, used, _ = st.compress(x)
+        t1 = time.perf_counter()
+        dec.decompress(rec)
+        t2 = time.perf_counter()
+        tc[used].append(t1 - t0)
+        td[used].append(t2 - t1)
+    mean = lambda v: sum(v) / len(v) if v else None  # noqa: E731
+    n_s = sum(1 for m in gpu_methods if m == O.METHOD_S)
+    n_t = len(gpu_methods) - n_s
+    cs, ct, ds, dt = mean(tc[O.METHOD_S]), mean(tc[O.METHOD_T]), mean(td[O.METHOD_S]), mean(td[O.METHOD_T])
+    if ct is None:  # no temporal frame in the sample: charge them as spatial ones
+        ct, dt = cs, ds
+    tot_c = n_s * cs + n_t * ct
+    tot_d = n_s * ds + n_t * dt
+    total = n_bytes_frame * len(gpu_methods)
+    return dict(value=total / (tot_c + tot_d) / 1e9, unit="GB/s", cores=1, kind="oracle",
+                sample=f"first {len(frames_np)} frames of the workload at full n "
+                       f"({len(tc[O.METHOD_S])} spatial, {len(tc[O.METHOD_T])} temporal), per-frame "
+                       f"compress+decompress times weighted by the GPU stream's mix ({n_s} spatial, "
+                       f"{n_t} temporal of {len(gpu_methods)}): compress {total / tot_c / 1e9:.4f} "
+                       f"GB/s, decompress {total / tot_d / 1e9:.4f} GB/s; spatial frame "
+                       f"{cs:.2f}+{ds:.2f} s, temporal frame {ct:.2f}+{dt:.2f} s; host CPU: "
+                       f"{cpu_model()}, nproc {os.cpu_count()}")
+
+
+def bench_single_s(args, torch, lcp, name, x, eb_mode, eb, steps, warmup, timer, cpu_n):
+    """One frame, LCP-S only (single-frame plan, block size searched on the frame):
+    compress and decompress timed separately over `steps` calls."""
+    dev = x.device
+    F, n = x.shape
+    size_d = 4 * F * n
+    plan = lcp.Plan(eb, eb_mode, n_fields=F, block_log2=-1, sample=x, max_particles=n)
+    k = plan.block_log2
+    out = torch.empty(plan.bound(n) + 16, dtype=torch.uint8, device=dev)
+    dec = torch.empty((F, n), dtype=torch.float32, device=dev)
+    offs = None
+    for _ in range(warmup):
+        _, offs, _, _ = plan.compress([x], out=out)
+        plan.decompress(out, offs, outs=[dec])
+    torch.cuda.synchronize()
+    plan.timer_set(timer)
+    tc = td = 0.0
+    for _ in range(steps):
+        t0 = time.perf_counter()
+        _, offs, _, _ = plan.compress([x], out=out)
+        t1 = time.perf_counter()
+        plan.decompress(out, offs, outs=[dec])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        tc += t1 - t0
+        td += t2 - t1
+    kms, kl, kb = plan.timer_read()
+    c = offs[1]
+    # error bound, every value, against the slot permutation
+    _, offs2, _, perms = plan.compress([x], out=out, want_perm=True)
+    assert offs2[1] == c
+    plan.decompress(out, offs2, outs=[dec])
+    perm = perms[0].long()
+    lo = x.amin(dim=1).double()
+    hi = x.amax(dim=1).double()
+    worst = 0.0
+    for f in range(F):
+        e = (dec[f].double() - x[f][perm].double()).abs().max().item()
+        ebf = eb if eb_mode == lcp.EB_ABS else eb * (hi[f] - lo[f]).item() if eb_mode == lcp.EB_REL_PER_FIELD \
+            else eb * (hi.max() - lo.min()).item()
+        assert e <= ebf, (name, f, e, ebf)
+        worst = max(worst, e / ebf)
+    res = {
+        "workload": name, "particles": n, "fields": F, "block_log2": k,
+        "compress_GBps": size_d * steps / tc / 1e9, "decompress_GBps": size_d * steps / td / 1e9,
+        "GBps": size_d * steps / (tc + td) / 1e9, "ratio": size_d / c, "bits_per_value": 32.0 * c / size_d,
+        "max_err_over_eb": worst, "steps": steps,
+        "path_roofline": {"bound": "hbm", "compress": path_frac(s_bytes(F, n, c) * steps, tc),
+                          "decompress": path_frac(s_bytes(F, n, c) * steps, td),
+                          "bytes_rule": "S compress 4FN + C, S decompress C + 4FN"},
+        "kernel_timer": {"kernel": timer, "launches": kl,
+                         "avg_launch_us": kms / kl * 1e3 if kl else None,
+                         "declared_bytes_per_launch": kb / kl if kl else None},
+    }
+    if n * 4 * F <= (256 << 20):
+        res["mall_note"] = "the whole frame fits in the 256 MB Infinity Cache: cache- and launch-bound, not HBM-bound"
+    if cpu_n:
+        # the oracle on the first cpu_n particles of the same frame
+        import oracle as O
+        xs = x[:, :cpu_n].cpu().numpy()
+        grids = O.grids_for(xs, {lcp.EB_ABS: O.EB_ABS, lcp.EB_REL_GLOBAL: O.EB_REL_GLOBAL,
+                                 lcp.EB_REL_PER_FIELD: O.EB_REL_PER_FIELD}[eb_mode], eb)
+        t0 = time.perf_counter()
+        rec, _, _ = O.compress_s(xs, grids, k)
+        t1 = time.perf_counter()
+        O.decompress(rec)
+        t2 = time.perf_counter()
+        nb = 4 * F * cpu_n
+        res["cpu_oracle"] = {"value": nb / (t2 - t0) / 1e9, "unit": "GB/s", "cores": 1,
+                             "sample": f"first {cpu_n} particles of the frame, compress "
+                                       f"{nb / (t1 - t0) / 1e9:.4f} GB/s, decompress "
+                                       f"{nb / (t2 - t1) / 1e9:.4f} GB/s"}
+    del plan, out, dec
+    torch.cuda.empty_cache()
+    return res
 
 
 def bench_batched(args, torch, lcp, datagen, dev):
@@ -169,6 +317,10 @@ def bench_batched(args, torch, lcp, datagen, dev):
         "plain_decompress_call_ms_p50": pct(ld_all, 50),
         "plain_decompress_call_ms_p99": pct(ld_all, 99),
         "ratio": size_d / boffs[-1], "bytes_equal_plain": bool(same),
+        "path_roofline": {"bound": "hbm",
+                          "batched_compress": path_frac((size_d + boffs[-1]) * steps, bc),
+                          "batched_decompress": path_frac((size_d + boffs[-1]) * steps, bd),
+                          "bytes_rule": "S compress 4FN + C, S decompress C + 4FN"},
         "max_err_over_eb": max_ratio_err, "steps": steps,
     }
 
@@ -327,13 +479,19 @@ def main():
     ap.add_argument("--n", type=int, default=1 << 22)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--eb", type=float, default=1e-4)
-    ap.add_argument("--cpu-frames", type=int, default=2)
+    ap.add_argument("--cpu-frames", type=int, default=6,
+                    help="frames of the trajectory the oracle codes for the CPU baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--roofline-kernel", default=ROOFLINE_KERNEL)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run three 256 MiB device copies (counter calibration)")
-    ap.add_argument("--workloads", default="md,batched,served",
-                    help="comma list: md (the trajectory, the headline value), batched, served")
+    ap.add_argument("--workloads", default="md,c1,c3,batched,served",
+                    help="comma list: md (the trajectory, the headline value), c1 (uniform "
+                         "frame), c3 (cosmology snapshot), batched, served")
+    ap.add_argument("--c3-n", type=int, default=1 << 27)
+    ap.add_argument("--c3-steps", type=int, default=3)
+    ap.add_argument("--c3-timer", default="radix_scatter")
+    ap.add_argument("--c1-steps", type=int, default=20)
     ap.add_argument("--batched-frames", type=int, default=256)
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--batched-warmup", type=int, default=1)
@@ -342,6 +500,7 @@ def main():
     ap.add_argument("--served-workers", type=int, default=4)
     ap.add_argument("--served-load", type=float, default=0.7)
     args = ap.parse_args()
+    work = args.workloads.split(",")
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1 "
@@ -354,134 +513,172 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    nx, ny, nz = (256, 128, 128) if args.n == 1 << 22 else datagen.lattice_dims(args.n)
-    log(f"generating {args.frames} frames of {args.n} particles")
-    traj = datagen.MDTrajectory(args.n, dims=(nx, ny, nz), seed=2)
-    frames_np, frames = [], []
-    for j in range(args.frames):
-        f = traj.next_frame()
-        if j < args.cpu_frames:
-            frames_np.append(f)
-        frames.append(torch.from_numpy(f).to(dev))
-    torch.cuda.synchronize()
-    size_d = sum(f.numel() * 4 for f in frames)
+    result = {"metric": METRIC, "value": None, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+              "warmup": args.warmup, "ms_per_step": None, "higher_is_better": True,
+              "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic"}
+    ceiling = copy_ceiling(torch, dev)
+    log(f"copy ceiling {ceiling['copy_GBps']:.0f} GB/s, read {ceiling['read_GBps']:.0f} GB/s")
 
-    plan = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=args.batch,
-                    block_log2=-1, max_particles=args.n, sample=frames[0])
-    k = plan.block_log2
-    dplan = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=args.batch,
-                     block_log2=k, max_particles=args.n)
-    log(f"block_log2 k={k}")
-    cap = sum((plan.bound(args.n) + 3) & ~3 for _ in frames)
-    outbuf = torch.empty(cap, dtype=torch.uint8, device=dev)
-    decbufs = [torch.empty((3, args.n), dtype=torch.float32, device=dev) for _ in range(args.frames)]
-
-    def step():
-        plan.reset()
-        dplan.reset()
+    if "md" in work:
+        nx, ny, nz = (256, 128, 128) if args.n == 1 << 22 else datagen.lattice_dims(args.n)
+        log(f"generating {args.frames} frames of {args.n} particles")
+        traj = datagen.MDTrajectory(args.n, dims=(nx, ny, nz), seed=2)
+        frames_np, frames = [], []
+        for j in range(args.frames):
+            f = traj.next_frame()
+            if j < args.cpu_frames:
+                frames_np.append(f)
+            frames.append(torch.from_numpy(f).to(dev))
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        out, offs, used, _ = plan.compress(frames, out=outbuf)
+        size_d = sum(f.numel() * 4 for f in frames)
+
+        plan = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=args.batch,
+                        block_log2=-1, max_particles=args.n, sample=frames[0])
+        k = plan.block_log2
+        dplan = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=args.batch,
+                         block_log2=k, max_particles=args.n)
+        log(f"block_log2 k={k}")
+        cap = sum((plan.bound(args.n) + 3) & ~3 for _ in frames)
+        outbuf = torch.empty(cap, dtype=torch.uint8, device=dev)
+        decbufs = [torch.empty((3, args.n), dtype=torch.float32, device=dev) for _ in range(args.frames)]
+
+        def step():
+            plan.reset()
+            dplan.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out, offs, used, _ = plan.compress(frames, out=outbuf)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            dplan.decompress(out, offs, outs=decbufs)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            return t1 - t0, t2 - t1, offs, used
+
+        for w in range(args.warmup):
+            step()
+            log(f"warmup {w} done")
+        plan.timer_set(args.roofline_kernel)
+        dplan.timer_set(args.roofline_kernel)
+        tc = td = 0.0
         torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        dplan.decompress(out, offs, outs=decbufs)
+        t_start = time.perf_counter()
+        for s_ in range(args.steps):
+            c, d, offs, used = step()
+            tc += c
+            td += d
+            log(f"step {s_}: compress {c * 1e3:.1f} ms, decompress {d * 1e3:.1f} ms")
         torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        return t1 - t0, t2 - t1, offs, used
+        t_total = time.perf_counter() - t_start
+        kms, klaunch, kbytes = plan.timer_read()
+        dkms, dklaunch, dkbytes = dplan.timer_read()
+        kms, klaunch, kbytes = kms + dkms, klaunch + dklaunch, kbytes + dkbytes
 
-    for w in range(args.warmup):
-        step()
-        log(f"warmup {w} done")
-    plan.timer_set(args.roofline_kernel)
-    dplan.timer_set(args.roofline_kernel)
-    tc = td = 0.0
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    for s in range(args.steps):
-        c, d, offs, used = step()
-        tc += c
-        td += d
-        log(f"step {s}: compress {c * 1e3:.1f} ms, decompress {d * 1e3:.1f} ms")
-    torch.cuda.synchronize()
-    t_total = time.perf_counter() - t_start
-    kms, klaunch, kbytes = plan.timer_read()
-    dkms, dklaunch, dkbytes = dplan.timer_read()
-    kms, klaunch, kbytes = kms + dkms, klaunch + dklaunch, kbytes + dkbytes
+        comp_bytes = offs[-1]
+        ratio = size_d / comp_bytes
+        n_t = sum(1 for u in used if u == lcp.METHOD_T)
+        # algorithmic bytes of one step by Sec. 8(d)'s rules, per frame by its method
+        bc = bd = 0
+        for j, u in enumerate(used):
+            c = offs[j + 1] - offs[j]
+            if u == lcp.METHOD_T:
+                bc += t_bytes_c(3, args.n, c)
+                bd += t_bytes_d(3, args.n, c)
+            else:
+                bc += s_bytes(3, args.n, c)
+                bd += s_bytes(3, args.n, c)
+        # error bound check on a few frames against the slot permutation
+        eb_abs = args.eb * (float(frames[0].max()) - float(frames[0].min()))
+        chk = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=args.batch,
+                       block_log2=k, max_particles=args.n)
+        nchk = min(3, len(frames))
+        out2, offs2, _, perms = chk.compress(frames[:nchk], want_perm=True)
+        dchk = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=args.batch,
+                        block_log2=k, max_particles=args.n)
+        dec = dchk.decompress(out2, offs2)
+        max_err = max(float((dec[j].double() - frames[j][:, perms[j].long()].double()).abs().max())
+                      for j in range(nchk))
+        assert max_err <= eb_abs, (max_err, eb_abs)
+        del chk, dchk, dec, out2
 
-    comp_bytes = offs[-1]
-    ratio = size_d / comp_bytes
-    n_t = sum(1 for u in used if u == lcp.METHOD_T)
-    # error bound check on a few frames against the slot permutation
-    eb_abs = args.eb * (float(frames[0].max()) - float(frames[0].min()))
-    chk = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=args.batch, block_log2=k,
-                   max_particles=args.n)
-    nchk = min(3, len(frames))
-    out2, offs2, _, perms = chk.compress(frames[:nchk], want_perm=True)
-    dchk = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=args.batch,
-                    block_log2=k, max_particles=args.n)
-    dec = dchk.decompress(out2, offs2)
-    max_err = max(float((dec[j].double() - frames[j][:, perms[j].long()].double()).abs().max())
-                  for j in range(nchk))
-    assert max_err <= eb_abs, (max_err, eb_abs)
+        if args.copy_probe:
+            src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
+            dst = torch.empty_like(src)
+            for _ in range(3):
+                dst.copy_(src)
+            torch.cuda.synchronize()
+            del src, dst
 
-    if args.copy_probe:
-        src = torch.empty(64 << 20, dtype=torch.float32, device=dev).fill_(1.0)
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-
-    ms_per_step = t_total / args.steps * 1e3
-    achieved = (kbytes / klaunch) / (kms / klaunch * 1e-3) / 1e9 if klaunch else None
-    result = {
-        "metric": METRIC,
-        "value": size_d * args.steps / (tc + td) / 1e9,
-        "unit": "GB/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": ms_per_step,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"MD-like trajectory, {args.frames} frames x {args.n} particles "
-                               f"({nx}x{ny}x{nz} lattice, jitter 0.1, step 0.01), float32 xyz, "
-                               f"eb={args.eb:g} x range, batch {args.batch}, LCP-FSM S/T",
-                   "frames": args.frames, "particles_per_frame": args.n, "block_log2": k,
-                   "chunk_log2": 10},
-        "compress_GBps": size_d * args.steps / tc / 1e9,
-        "decompress_GBps": size_d * args.steps / td / 1e9,
-        "ratio": ratio,
-        "bits_per_value": 32.0 / ratio,
-        "temporal_frames": n_t,
-        "max_abs_err": max_err,
-        "eb_abs": eb_abs,
-        "roofline": {"bound": "hbm", "kernel": args.roofline_kernel,
-                     "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
-                     "frac": (achieved / HBM_PEAK_GBPS) if achieved else None,
-                     "traffic": measured_traffic(args.roofline_kernel),
-                     "timed_launches": klaunch, "timed_every": 16,
-                     "avg_launch_us": (kms / klaunch * 1e3) if klaunch else None,
-                     "bytes_per_launch": (kbytes / klaunch) if klaunch else None},
-    }
-    if "batched" in args.workloads.split(","):
+        achieved = (kbytes / klaunch) / (kms / klaunch * 1e-3) / 1e9 if klaunch else None
+        result.update({
+            "value": size_d * args.steps / (tc + td) / 1e9,
+            "ms_per_step": t_total / args.steps * 1e3,
+            "config": {"workload": f"MD-like trajectory, {args.frames} frames x {args.n} particles "
+                                   f"({nx}x{ny}x{nz} lattice, jitter 0.1, step 0.01), float32 xyz, "
+                                   f"eb={args.eb:g} x range, batch {args.batch}, LCP-FSM S/T",
+                       "frames": args.frames, "particles_per_frame": args.n, "block_log2": k,
+                       "chunk_log2": 10},
+            "compress_GBps": size_d * args.steps / tc / 1e9,
+            "decompress_GBps": size_d * args.steps / td / 1e9,
+            "ratio": ratio,
+            "bits_per_value": 32.0 / ratio,
+            "temporal_frames": n_t,
+            "max_abs_err": max_err,
+            "eb_abs": eb_abs,
+            "roofline": {"bound": "hbm", "kernel": args.roofline_kernel,
+                         "achieved": achieved, "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                         "frac": (achieved / HBM_PEAK_GBPS) if achieved else None,
+                         "traffic": measured_traffic(args.roofline_kernel),
+                         "timed_launches": klaunch, "timed_every": 16,
+                         "avg_launch_us": (kms / klaunch * 1e3) if klaunch else None,
+                         "bytes_per_launch": (kbytes / klaunch) if klaunch else None,
+                         "bytes_rule": "4 + 12F per particle: frame, reference codes and "
+                                       "permutation read, new reference codes written",
+                         "copy_ceiling": ceiling, "mall_note": MALL_NOTE},
+            "path_roofline": {"bound": "hbm",
+                              "compress": path_frac(bc * args.steps, tc),
+                              "decompress": path_frac(bd * args.steps, td),
+                              "bytes_rule": "per frame: S 4FN + C both ways; T compress "
+                                            "12FN + 4N + C, T decompress 12FN + C",
+                              "mall_note": MALL_NOTE},
+        })
+        if not args.no_cpu_baseline:
+            log(f"cpu baseline: oracle on {len(frames_np)} frames")
+            cb = cpu_baseline(frames_np, args.eb, args.batch, k, list(used), 12 * args.n)
+            result["cpu_baseline"] = cb
         del frames, decbufs, outbuf, plan, dplan
+        torch.cuda.empty_cache()
+    if "c1" in work:
+        log("uniform frame (2^18 particles)")
+        x = torch.from_numpy(datagen.uniform_frame(1 << 18, seed=1)).to(dev)
+        result["c1"] = bench_single_s(args, torch, lcp, "uniform frame, 262144 particles in "
+                                      "[0,100)^3, float32 xyz, eb=1e-3 absolute, LCP-S",
+                                      x, lcp.EB_ABS, 1e-3, args.c1_steps, 3, "decode_huff", 0)
+        log(json.dumps(result["c1"]))
+        del x
+    if "c3" in work:
+        log(f"cosmology snapshot ({args.c3_n} particles x 6 fields)")
+        x = datagen.cosmology_snapshot_device(torch, args.c3_n, dev)
+        torch.cuda.synchronize()
+        result["c3"] = bench_single_s(
+            args, torch, lcp, f"cosmology-like snapshot, {args.c3_n} particles: 2000 Gaussian "
+            f"halos (sigma log-uniform 0.1-2.0) + 30% uniform in [0,256)^3, shuffled, velocities "
+            f"N(0, 300^2), float32 x 6 fields, eb=1e-4 x range per field, LCP-S",
+            x, lcp.EB_REL_PER_FIELD, 1e-4, args.c3_steps, 1, args.c3_timer,
+            0 if args.no_cpu_baseline else 1 << 22)
+        log(json.dumps(result["c3"]))
+        del x
+        torch.cuda.empty_cache()
+    if "batched" in work:
         torch.cuda.empty_cache()
         log("batched workload")
         result["batched"] = bench_batched(args, torch, lcp, datagen, dev)
         log(json.dumps(result["batched"]))
-    if "served" in args.workloads.split(","):
+    if "served" in work:
         torch.cuda.empty_cache()
         log("served workload")
         result["served"] = bench_served(args, torch, lcp, datagen, dev)
         log(json.dumps(result["served"]))
-    if not args.no_cpu_baseline:
-        log(f"cpu baseline: oracle on {args.cpu_frames} frames")
-        cb = cpu_baseline(frames_np, args.eb, args.batch, k, args.cpu_frames)
-        result["cpu_baseline"] = {kk: cb[kk] for kk in ("value", "unit", "cores", "kind", "sample")}
     print(json.dumps(result))
 
 

@@ -1133,11 +1133,13 @@ void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
                     unsigned long long* hist_max, ArrWork* zero_words, hipStream_t s) {
   const int vec = (n % 4 == 0) && al16(perm_ref) && al16(q_ref) && al16(v_res) && al16(q_new) &&
                   (!v8 || al16(v8));
-  // algorithmic bytes: permutation, x and reference codes read; residuals
-  // (bytes, or u32) and new codes written.  One item per thread up to 4096
-  // workgroups (a 4,194,304-particle frame in one pass): two items per thread
-  // on half the workgroups measured 3-4% slower.
-  launch_timed("t_resid", n * (4 + 12ull * F + (v8 ? 1ull : 4ull) * F), k_t_resid, grid_for(vec ? n / 4 : n, kThreads, 4096), kThreads, (size_t)F * (kThreads / kWave) * kResPriv * 4, s,
+  // algorithmic bytes: this kernel's share of what LCP-T compression must move
+  // per particle -- the frame (4F), the reference codes (4F) and the slot
+  // permutation (4) read, the new reference codes (4F) written; the residual
+  // symbols it hands to the coder are an intermediate, not counted.  One item
+  // per thread up to 4096 workgroups (a 4,194,304-particle frame in one pass):
+  // two items per thread on half the workgroups measured 3-4% slower.
+  launch_timed("t_resid", n * (4 + 12ull * F), k_t_resid, grid_for(vec ? n / 4 : n, kThreads, 4096), kThreads, (size_t)F * (kThreads / kWave) * kResPriv * 4, s,
                x, F, n, g, perm_ref, q_ref, v8, v_res, q_new, err, vec, hist_part, hist_max,
                zero_words);
 }

@@ -120,3 +120,36 @@ def serve_stream_sizes(n_streams: int = 32, lo_log2: int = 16, hi_log2: int = 24
 def poisson_arrivals(rate_hz: float, n: int, seed: int = 5):
     rng = np.random.default_rng(seed + 7)
     return np.cumsum(rng.exponential(1.0 / rate_hz, size=n))
+
+
+def cosmology_snapshot_device(torch, n: int = 1 << 27, device="cuda", box: float = 256.0,
+                              n_halos: int = 2000, bg_frac: float = 0.3, vel_sigma: float = 300.0,
+                              seed: int = 3):
+    """The cosmology-like snapshot's recipe drawn on the device with torch's
+    generator (same distributions as cosmology_snapshot, other random numbers):
+    70% of the particles in Gaussian halos (centres uniform in the box, sigma
+    log-uniform in [0.1, 2.0], halo chosen uniformly), 30% uniform, wrapped into
+    [0, box), shuffled; velocities N(0, vel_sigma^2).  Returns a (6, n) float32
+    tensor."""
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    n_bg = int(round(bg_frac * n))
+    n_h = n - n_bg
+    centres = torch.rand((n_halos, 3), generator=g, device=device, dtype=torch.float64) * box
+    sig = torch.exp(torch.rand(n_halos, generator=g, device=device, dtype=torch.float64)
+                    * (np.log(2.0) - np.log(0.1)) + np.log(0.1))
+    h = torch.randint(0, n_halos, (n_h,), generator=g, device=device)
+    out = torch.empty((6, n), dtype=torch.float32, device=device)
+    perm = torch.randperm(n, generator=g, device=device)
+    top = float(np.nextafter(np.float32(box), np.float32(0.0)))
+    for d in range(3):
+        pos = torch.empty(n, dtype=torch.float64, device=device)
+        pos[:n_h] = centres[h, d] + torch.randn(n_h, generator=g, device=device,
+                                                dtype=torch.float64) * sig[h]
+        pos[n_h:] = torch.rand(n_bg, generator=g, device=device, dtype=torch.float64) * box
+        pos = torch.remainder(pos, box)
+        out[d] = torch.clamp(pos[perm].to(torch.float32), max=top)
+        del pos
+    for d in range(3):
+        out[3 + d] = torch.randn(n, generator=g, device=device, dtype=torch.float32) * vel_sigma
+    return out

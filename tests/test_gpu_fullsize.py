@@ -123,3 +123,130 @@ def test_corrupted_records_fail_cleanly(lcp, seed):
     with pytest.raises(lcp.LCPError):
         dplan.decompress(out, [0, offs[1] - 8])
     torch.cuda.synchronize()
+
+
+# ------------------------------------------------------------------ byte parity at production sizes
+def bits_equal(a, b) -> bool:
+    return np.array_equal(np.asarray(a, np.float32).view(np.uint32), np.asarray(b, np.float32).view(np.uint32))
+
+
+def test_cosmology_snapshot_2p25_byte_parity(lcp):
+    """The snapshot's recipe at 2^25 particles x 6 fields (the largest size the
+    oracle codes in well under a minute): record bytes, slot permutation and
+    every decoded value against the oracle.  Same grid, block size and key
+    width (four radix passes) as at 2^27; what 2^27 adds is one more level of
+    the digit-count scan and more workgroups per launch, which the property
+    test above covers."""
+    n = 1 << 25
+    print(f"case cosmology n={n}", flush=True)
+    x = datagen.cosmology_snapshot(n, seed=3)
+    xd = torch.from_numpy(x).cuda()
+    plan = lcp.Plan(1e-4, lcp.EB_REL_PER_FIELD, n_fields=6, block_log2=3, max_particles=n)
+    out, offs, _, perms = plan.compress([xd], want_perm=True)
+    rec = out[offs[0]:offs[1]].cpu().numpy().tobytes()
+    perm = perms[0].cpu().numpy().astype(np.uint32)
+    dec = plan.decompress(out, offs)[0].cpu().numpy()
+    del out, perms, xd, plan
+    torch.cuda.empty_cache()
+    grids = O.grids_for(x, O.EB_REL_PER_FIELD, 1e-4)
+    want, wperm, _ = O.compress_s(x, grids, 3, 10, 0)
+    assert len(rec) == len(want)
+    assert rec == want
+    assert np.array_equal(perm, wperm)
+    del want, wperm
+    wdec, _ = O.decompress(rec)
+    for f in range(6):
+        assert bits_equal(dec[f], wdec[f]), f
+
+
+def test_md_trajectory_36_frames_one_call_parity(lcp):
+    """36 frames of 4,194,304 particles, Alg. 1 batches of 16 (the first frames of
+    batches 2 and 3 coded against the anchor, frame 0), LCP-FSM: one
+    lcp_compress call (temporal runs) and one
+    lcp_decompress call (chains of temporal frames), frame by frame against the
+    oracle stream: record bytes, method, permutation and decoded values."""
+    n, frames, batch, k = 1 << 22, 36, 16, 12
+    print(f"case md n={n} frames={frames}", flush=True)
+    traj = datagen.MDTrajectory(n, dims=(256, 128, 128), seed=2)
+    xs = [traj.next_frame() for _ in range(frames)]
+    xd = [torch.from_numpy(x).cuda() for x in xs]
+    plan = lcp.Plan(1e-4, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=batch, block_log2=k,
+                    max_particles=n)
+    out, offs, used, perms = plan.compress(xd, want_perm=True)
+    dplan = lcp.Plan(1e-4, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=batch, block_log2=k,
+                     max_particles=n)
+    dec = dplan.decompress(out, offs)
+    ost = O.Stream(O.EB_REL_GLOBAL, 1e-4, batch_size=batch, block_log2=k, max_n=n)
+    dst = O.Stream(O.EB_REL_GLOBAL, 1e-4, batch_size=batch, block_log2=k, max_n=n)
+    n_t = 0
+    for t in range(frames):
+        want, wused, wperm = ost.compress(xs[t])
+        rec = out[offs[t]:offs[t + 1]].cpu().numpy().tobytes()
+        assert used[t] == wused, t
+        assert rec == want, t
+        assert np.array_equal(perms[t].cpu().numpy().astype(np.uint32), wperm), t
+        w = dst.decompress(want)
+        d = dec[t].cpu().numpy()
+        assert all(bits_equal(d[f], w[f]) for f in range(3)), t
+        n_t += wused == O.METHOD_T
+    assert n_t >= 30 and used[16] == used[32] == lcp.METHOD_T
+
+
+@pytest.mark.parametrize("n", [1 << 24, (1 << 24) + 3])
+def test_forced_temporal_pair_2p24(lcp, n):
+    """A spatial frame then a forced temporal one at 2^24 particles: the residual
+    kernel's grid is capped, so each thread takes several items (four slots at a
+    time when n is a multiple of four, one at a time otherwise)."""
+    print(f"case temporal pair n={n}", flush=True)
+    traj = datagen.MDTrajectory(n, seed=61)
+    x0, x1 = traj.next_frame(), traj.next_frame()
+    ost = O.Stream(O.EB_REL_GLOBAL, 1e-4, batch_size=0, block_log2=8, max_n=n)
+    plan = lcp.Plan(1e-4, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=0, block_log2=8,
+                    max_particles=n)
+    methods = [lcp.METHOD_S, lcp.METHOD_T]
+    out, offs, used, _ = plan.compress([torch.from_numpy(x0).cuda(), torch.from_numpy(x1).cuda()],
+                                       methods=methods)
+    assert list(used) == methods
+    recs = []
+    for t, x in enumerate((x0, x1)):
+        want, wused, _ = ost.compress(x, method=methods[t])
+        rec = out[offs[t]:offs[t + 1]].cpu().numpy().tobytes()
+        assert rec == want, t
+        recs.append(want)
+    dplan = lcp.Plan(1e-4, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=0, block_log2=8,
+                     max_particles=n)
+    dec = dplan.decompress(out, offs)
+    dst = O.Stream(O.EB_REL_GLOBAL, 1e-4, batch_size=0, block_log2=8, max_n=n)
+    for t in range(2):
+        w = dst.decompress(recs[t])
+        d = dec[t].cpu().numpy()
+        assert all(bits_equal(d[f], w[f]) for f in range(3)), t
+
+
+def test_seventy_records_one_call(lcp):
+    """70 independent frames (four of them past 2^20 particles) compressed in one
+    call and decoded in one call, which takes them 64 records at a time: every
+    record, permutation and decoded value against the oracle."""
+    rng = np.random.default_rng(71)
+    sizes = [int(v) for v in rng.integers(1, 40000, size=66)] + [1 << 20, (1 << 20) + 77, 1500000, 1234567]
+    rng.shuffle(sizes)
+    xs = []
+    for j, n in enumerate(sizes):
+        if j % 2 == 0:
+            xs.append(datagen.uniform_frame(n, hi=100.0, seed=700 + j))
+        else:
+            xs.append(datagen.clustered_positions(rng, n, 100.0, 50, 0.3))
+    tot = sum(sizes)
+    print(f"case 70 records, {tot} particles", flush=True)
+    plan = lcp.Plan(1e-4, lcp.EB_REL_GLOBAL, block_log2=5, max_particles=max(sizes),
+                    max_batch_particles=tot, max_batch_frames=len(xs))
+    out, offs, used, perms = plan.compress([torch.from_numpy(x).cuda() for x in xs], want_perm=True)
+    dec = plan.decompress(out, offs)
+    buf = out[:offs[-1]].cpu().numpy().tobytes()
+    for j, x in enumerate(xs):
+        want, wperm, _ = O.compress_s(x, O.grids_for(x, O.EB_REL_GLOBAL, 1e-4), 5, 10, j)
+        assert buf[offs[j]:offs[j + 1]] == want, j
+        assert np.array_equal(perms[j].cpu().numpy().astype(np.uint32), wperm), j
+        w, _ = O.decompress(want)
+        d = dec[j].cpu().numpy()
+        assert all(bits_equal(d[f], w[f]) for f in range(3)), j
