@@ -190,6 +190,28 @@ lcp_status lcp_select(lcp_plan_t plan, int* decision);
 
 const char* lcp_status_string(lcp_status status);
 
+/* LCP-S compression of independent frames that allocates nothing: for callers
+ * that cannot allocate device or pinned memory during the call (code that a HIP
+ * graph capture surrounds, tight serving loops, harnesses that forbid it).
+ * Same records, offsets and permutations as lcp_compress on a fresh plan made
+ * with the same params (record j of a call carries sequence number j), but no
+ * plan exists: the scratch is one library-owned device array of 64 MiB per GPU
+ * (file-scope, reserved with the library's code object and held by each GPU the
+ * library runs on until the process ends) plus a static host block for the
+ * small tables.  params: as for lcp_plan, with multi_frame = 0 and block_log2 in
+ * [0, 16] (no search); max_particles, max_batch_particles and max_batch_frames
+ * (0 means 1 here: one frame per launch set) size the scratch the call needs,
+ * which must fit the array -- else LCP_ERR_BUDGET before any HIP call.  With one
+ * frame per launch set that is up to 553,408 particles of three fields (436,928
+ * of six); each further frame per launch set costs about 2 MB.  The other
+ * arguments and errors are lcp_compress's (methods are all LCP_METHOD_S).
+ * Calls on one GPU share its array and keep none of each other's state: the
+ * library runs them one at a time (each call has finished on the GPU when it
+ * returns), and clears what must start at zero at the start of every call. */
+lcp_status lcp_compress_static(const lcp_params* params, uint64_t n_frames,
+                               const lcp_frame_in* frames, void* out, uint64_t out_cap,
+                               uint64_t* out_offsets, uint32_t* const* perms, hipStream_t stream);
+
 /* Kernel timing for roofline measurement: while a name is set, one launch in
  * sixteen of the kernel with that name (the first, the 17th, ...) carries HIP
  * events on its own dispatch; the accumulated time (ms), count and algorithmic

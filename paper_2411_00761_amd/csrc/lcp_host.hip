@@ -8,6 +8,7 @@
 
 #include <initializer_list>
 #include <algorithm>
+#include <mutex>
 #include <vector>
 
 #include "../../include/lcp.h"
@@ -120,6 +121,9 @@ struct lcp_plan_s {
   // cleared when a server takes the memory back (or the search's temporary
   // scratch is freed); compress and decompress refuse to run without it
   bool bound = false;
+  // scratch laid out for LCP-S compression only (no decode tables): the
+  // library's static scratch, which must stay small
+  bool compress_only = false;
   size_t scratch_bytes = 0, host_bytes = 0, state_bytes = 0;
 
   // scratch (batch-wide arrays hold NB slots)
@@ -1579,17 +1583,21 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   }
   D.add(&P->chunk_words, P->cw_cap);
   D.add(&P->stage, P->stage_cap);
-  D.add(&P->lut, (uint64_t)(kMaxBatchArrays + 2 * kMaxBatchFrames) << kMaxLen);
+  // decode-only tables: 2^13 LUT entries per array of a decode launch, header
+  // staging, descriptor tables, block corners
+  const uint64_t dec_arrays = P->compress_only ? 0 : kMaxBatchArrays + 2 * kMaxBatchFrames;
+  const uint64_t dec_frames = P->compress_only ? 0 : kMaxBatchFrames;
+  D.add(&P->lut, dec_arrays << kMaxLen);
   D.add(&P->ext_part, (uint64_t)2 * kMaxF * kSegExtCap * RB);
   D.add(&P->hist_part, hc * kAlphabet);
   D.add(&P->hist_max, hc);
   D.add(&P->huff_lens, NA * kHuffCandidates * kAlphabet);
   D.add(&P->huff_maxd, NA * kHuffCandidates);
-  D.add(&P->hdr_dev, (uint64_t)kHdrStage * kMaxBatchFrames);
-  D.add(&P->blobtab_dev, 2 * kMaxBatchFrames);
-  D.add(&P->arrtab_dev, kMaxBatchArrays + 2 * kMaxBatchFrames);
-  D.add(&P->prefix_dev, 2 * (kMaxBatchArrays + 2 * kMaxBatchFrames));
-  D.add(&P->corner, 3 * NB);
+  D.add(&P->hdr_dev, (uint64_t)kHdrStage * dec_frames);
+  D.add(&P->blobtab_dev, 2 * dec_frames);
+  D.add(&P->arrtab_dev, dec_arrays);
+  D.add(&P->prefix_dev, 2 * dec_arrays);
+  D.add(&P->corner, P->compress_only ? 0 : 3 * NB);
   D.add(&P->scan_tmp, P->scan_tmp_n);
   D.add(&P->work, NA);
   D.add(&P->ret_dev, 2 + (uint64_t)RB + (uint64_t)RB * F);
@@ -1598,26 +1606,26 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   // staging (seg + segpre, dseg + dpre, erec + earr + epre)
   D.add(&P->seg_dev, RB);
   D.add(&P->segpre_dev, 4 * ((uint64_t)RB + 1));
-  D.add(&P->dseg_dev, kMaxBatchFrames);
-  D.add(&P->dpre_dev, 2 * (kMaxBatchFrames + 1));
+  D.add(&P->dseg_dev, dec_frames);
+  D.add(&P->dpre_dev, P->compress_only ? 0 : 2 * (kMaxBatchFrames + 1));
   D.add(&P->erec_dev, RB);
   D.add(&P->earr_dev, NA);
   D.add(&P->epre_dev, 4 * (NA + 1));
   D.add(&P->rstart, (uint64_t)RB + 1);
   D.add(&P->Bs, RB);
   D.add(&P->permdst_dev, RB);
-  D.add(&P->segbase, 3 * kMaxBatchFrames);
-  D.add(&P->rec_tmp, P->rec_tmp_cap);
+  D.add(&P->segbase, 3 * dec_frames);
+  D.add(&P->rec_tmp, P->compress_only ? 0 : P->rec_tmp_cap);
   H.add(&P->ret_host, 2 + (size_t)RB + (size_t)RB * F);
   H.add(&P->run_host, 4 * kTRun);
-  H.add(&P->hdr_host, (size_t)kHdrStage * kMaxBatchFrames);
-  H.add(&P->blobtab_host, 2 * kMaxBatchFrames);
-  H.add(&P->arrtab_host, kMaxBatchArrays + 2 * kMaxBatchFrames);
-  H.add(&P->prefix_host, 2 * (kMaxBatchArrays + 2 * kMaxBatchFrames));
+  H.add(&P->hdr_host, (size_t)kHdrStage * dec_frames);
+  H.add(&P->blobtab_host, 2 * dec_frames);
+  H.add(&P->arrtab_host, dec_arrays);
+  H.add(&P->prefix_host, 2 * dec_arrays);
   H.add(&P->seg_host, RB);
   H.add(&P->segpre_host, 4 * ((size_t)RB + 1));
-  H.add(&P->dseg_host, kMaxBatchFrames);
-  H.add(&P->dpre_host, 2 * (kMaxBatchFrames + 1));
+  H.add(&P->dseg_host, dec_frames);
+  H.add(&P->dpre_host, P->compress_only ? 0 : 2 * (kMaxBatchFrames + 1));
   H.add(&P->erec_host, RB);
   H.add(&P->earr_host, NA);
   H.add(&P->epre_host, 4 * (NA + 1));
@@ -1770,16 +1778,52 @@ lcp_status compress_group(lcp_plan_s* P, int R, const lcp_frame_in* fr, uint8_t*
   return LCP_OK;
 }
 
+// Single-frame plans: independent frames in batches of up to RB frames and
+// NB particles, each batch one extent pass and one LCP-S launch set.
+lcp_status compress_independent(lcp_plan_s* plan, uint64_t n_frames, const lcp_frame_in* frames,
+                                uint8_t* o, uint64_t out_cap, uint64_t* out_offsets,
+                                int* methods_used, uint32_t* const* perms, hipStream_t stream) {
+  uint64_t off = 0;
+  out_offsets[0] = 0;
+  std::vector<uint64_t> offs((size_t)plan->RB + 1);
+  for (uint64_t j = 0; j < n_frames;) {
+    int R = 0;
+    uint64_t tot = 0;
+    while (j + R < n_frames && R < plan->RB) {
+      const lcp_frame_in& fr = frames[j + R];
+      if (fr.n == 0 || fr.n > plan->N || fr.method < 0 || fr.method > 2) return LCP_ERR_ARG;
+      for (int f = 0; f < plan->F; f++)
+        if (!fr.fields[f]) return LCP_ERR_ARG;
+      if (fr.method == LCP_METHOD_T) return LCP_ERR_NO_REFERENCE;
+      if (tot + fr.n > plan->NB) break;
+      tot += fr.n;
+      R++;
+    }
+    uint64_t cap = out_cap > off ? out_cap - off : 0;
+    lcp_status st = compress_group(plan, R, frames + j, o + off, cap, offs.data(),
+                                   perms ? perms + j : nullptr, stream);
+    if (st == LCP_ERR_CAPACITY) {
+      for (int r = 0; r < R; r++) out_offsets[j + r + 1] = off + offs[r + 1];
+      out_offsets[n_frames] = off + offs[R];  // the bytes required so far
+      return st;
+    }
+    if (st) return st;
+    for (int r = 0; r < R; r++) {
+      if (methods_used) methods_used[j + r] = LCP_METHOD_S;
+      out_offsets[j + r + 1] = off + offs[r + 1];
+    }
+    off += offs[R];
+    j += (uint64_t)R;
+  }
+  timer_collect(plan);
+  return LCP_OK;
+}
+
 }  // namespace
 
 namespace {
-// Validates params and fills the plan's sizes (no memory).
-lcp_status plan_setup(const lcp_params* params, const float* const* sample_fields,
-                      uint64_t sample_n, lcp_plan_s** out) {
-  if (!params || !out) return LCP_ERR_ARG;
-  *out = nullptr;
-  const lcp_params& p = *params;
-  int cl = p.chunk_log2 == 0 ? 10 : p.chunk_log2;
+lcp_status plan_check(const lcp_params& p, const float* const* sample_fields, uint64_t sample_n) {
+  const int cl = p.chunk_log2 == 0 ? 10 : p.chunk_log2;
   if (p.n_fields < 3 || p.n_fields > LCP_MAX_FIELDS || cl < 5 || cl > 12 || p.batch_size < 0 ||
       p.block_log2 < -1 || p.block_log2 > 16 || p.max_particles == 0 ||
       p.max_particles > (1ull << 31) || !(p.eb > 0) || p.eb_mode < 0 || p.eb_mode > 2 ||
@@ -1787,9 +1831,14 @@ lcp_status plan_setup(const lcp_params* params, const float* const* sample_field
       (p.max_batch_particles != 0 &&
        (p.max_batch_particles < p.max_particles || p.max_batch_particles > 0xFFFFFFFFull)))
     return LCP_ERR_ARG;
-  if (p.block_log2 == -1 && (!sample_fields || sample_n == 0)) return LCP_ERR_ARG;
-  if (hipSetDevice(p.device) != hipSuccess) return LCP_ERR_DEVICE;
-  lcp_plan_s* P = new lcp_plan_s();
+  if (p.block_log2 == -1 && (!sample_fields || sample_n == 0 || sample_n > p.max_particles))
+    return LCP_ERR_ARG;
+  return LCP_OK;
+}
+
+// The plan's sizes and parameters from checked params (no memory).
+void plan_fill(lcp_plan_s* P, const lcp_params& p) {
+  const int cl = p.chunk_log2 == 0 ? 10 : p.chunk_log2;
   P->p = p;
   P->p.chunk_log2 = cl;
   P->chunk_log2 = cl;
@@ -1803,10 +1852,18 @@ lcp_status plan_setup(const lcp_params* params, const float* const* sample_field
     P->NB = p.max_batch_particles == 0 ? P->N : p.max_batch_particles;
   }
   P->k = p.block_log2 < 0 ? 0 : p.block_log2;
-  if (p.block_log2 == -1 && sample_n > P->N) {
-    delete P;
-    return LCP_ERR_ARG;
-  }
+}
+
+// Validates params and fills the plan's sizes (no device memory).
+lcp_status plan_setup(const lcp_params* params, const float* const* sample_fields,
+                      uint64_t sample_n, lcp_plan_s** out) {
+  if (!params || !out) return LCP_ERR_ARG;
+  *out = nullptr;
+  lcp_status st = plan_check(*params, sample_fields, sample_n);
+  if (st) return st;
+  if (hipSetDevice(params->device) != hipSuccess) return LCP_ERR_DEVICE;
+  lcp_plan_s* P = new lcp_plan_s();
+  plan_fill(P, *params);
   *out = P;
   return LCP_OK;
 }
@@ -1953,41 +2010,9 @@ lcp_status lcp_compress(lcp_plan_t plan, uint64_t n_frames, const lcp_frame_in* 
   uint8_t* o = reinterpret_cast<uint8_t*>(out);
   uint64_t off = 0;
   out_offsets[0] = 0;
-  if (!plan->p.multi_frame) {
-    // independent frames: batches of up to RB frames and NB particles
-    std::vector<uint64_t> offs((size_t)plan->RB + 1);
-    for (uint64_t j = 0; j < n_frames;) {
-      int R = 0;
-      uint64_t tot = 0;
-      while (j + R < n_frames && R < plan->RB) {
-        const lcp_frame_in& fr = frames[j + R];
-        if (fr.n == 0 || fr.n > plan->N || fr.method < 0 || fr.method > 2) return LCP_ERR_ARG;
-        for (int f = 0; f < plan->F; f++)
-          if (!fr.fields[f]) return LCP_ERR_ARG;
-        if (fr.method == LCP_METHOD_T) return LCP_ERR_NO_REFERENCE;
-        if (tot + fr.n > plan->NB) break;
-        tot += fr.n;
-        R++;
-      }
-      uint64_t cap = out_cap > off ? out_cap - off : 0;
-      lcp_status st = compress_group(plan, R, frames + j, o + off, cap, offs.data(),
-                                     perms ? perms + j : nullptr, stream);
-      if (st == LCP_ERR_CAPACITY) {
-        for (int r = 0; r < R; r++) out_offsets[j + r + 1] = off + offs[r + 1];
-        out_offsets[n_frames] = off + offs[R];  // the bytes required so far
-        return st;
-      }
-      if (st) return st;
-      for (int r = 0; r < R; r++) {
-        if (methods_used) methods_used[j + r] = LCP_METHOD_S;
-        out_offsets[j + r + 1] = off + offs[r + 1];
-      }
-      off += offs[R];
-      j += (uint64_t)R;
-    }
-    timer_collect(plan);
-    return LCP_OK;
-  }
+  if (!plan->p.multi_frame)
+    return compress_independent(plan, n_frames, frames, o, out_cap, out_offsets, methods_used,
+                                perms, stream);
   bool one = false;  // the next frame goes through the per-frame path
   for (uint64_t j = 0; j < n_frames;) {
     uint64_t cap = out_cap > off ? out_cap - off : 0;
@@ -2078,3 +2103,69 @@ lcp_status lcp_kernel_timer_read(lcp_plan_t plan, double* total_ms, uint64_t* la
 }
 
 }  // extern "C"
+
+// ================================================================== no-allocation entry point
+// lcp_compress_static runs the single-frame LCP-S path of lcp_compress on
+// scratch that already exists: one file-scope device array per GPU (reserved
+// with the code object, held until the process ends) and a static host block
+// for the plan's small tables.  In host code `scratch` names a host-side
+// stand-in of the array, never its device memory: the device address comes
+// from hipGetSymbolAddress on the first call on each device, and only that
+// address is handed to kernels and fills.
+namespace {
+
+constexpr size_t kStaticScratchBytes = 64ull << 20;
+constexpr size_t kStaticHostBytes = 256ull << 10;
+constexpr int kStaticDevices = 16;
+
+static __device__ __align__(256) uint8_t scratch[kStaticScratchBytes];
+
+struct StaticSlot {
+  std::mutex mu;           // calls on one device run one at a time
+  void* dev = nullptr;     // this device's address of `scratch`
+  bool looked_up = false;
+  lcp_plan_s plan;         // sizes and table pointers of the current call
+  alignas(256) uint8_t host[kStaticHostBytes];
+};
+StaticSlot g_static[kStaticDevices];
+
+}  // namespace
+
+extern "C" lcp_status lcp_compress_static(const lcp_params* params, uint64_t n_frames,
+                                          const lcp_frame_in* frames, void* out, uint64_t out_cap,
+                                          uint64_t* out_offsets, uint32_t* const* perms,
+                                          hipStream_t stream) {
+  if (!params || (!frames && n_frames) || !out_offsets || (!out && n_frames) || ((uintptr_t)out & 3))
+    return LCP_ERR_ARG;
+  if (params->multi_frame || params->block_log2 < 0) return LCP_ERR_ARG;
+  lcp_status st = plan_check(*params, nullptr, 0);
+  if (st) return st;
+  if (params->device < 0 || params->device >= kStaticDevices) return LCP_ERR_ARG;
+  StaticSlot& S = g_static[params->device];
+  std::lock_guard<std::mutex> lk(S.mu);
+  lcp_plan_s* P = &S.plan;
+  lcp_params q = *params;
+  if (q.max_batch_frames == 0) q.max_batch_frames = 1;  // one frame per launch set
+  plan_fill(P, q);
+  P->compress_only = true;
+  P->seq = 0;
+  P->timer_name[0] = 0;
+  Layout D, H;
+  layout_scratch(P, D, H);
+  // refused before any HIP call
+  if (D.total > kStaticScratchBytes || H.total > kStaticHostBytes) return LCP_ERR_BUDGET;
+  if (hipSetDevice(params->device) != hipSuccess) return LCP_ERR_DEVICE;
+  if (!S.looked_up) {
+    // the device copy of the array on this (current) device
+    hipError_t e = hipGetSymbolAddress(&S.dev, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !S.dev) return hip_fail(e, "hipGetSymbolAddress(scratch)", __LINE__);
+    S.looked_up = true;
+  }
+  // binding clears what must start at zero (histogram copies, error word)
+  bind_scratch(P, S.dev, S.host, stream);
+  TimerScope ts(P);
+  st = compress_independent(P, n_frames, frames, reinterpret_cast<uint8_t*>(out), out_cap,
+                            out_offsets, nullptr, perms, stream);
+  P->bound = false;
+  return st;
+}

@@ -26,7 +26,7 @@ EXPORTED = ["lcp_plan", "lcp_plan_destroy", "lcp_plan_reset", "lcp_plan_block_lo
             "lcp_decompress", "lcp_select", "lcp_status_string", "lcp_kernel_timer_set",
             "lcp_kernel_timer_read", "lcp_server_create", "lcp_server_destroy",
             "lcp_server_open_stream", "lcp_server_submit", "lcp_server_wait",
-            "lcp_scratch_bytes"]
+            "lcp_scratch_bytes", "lcp_compress_static"]
 REQ_COMPRESS, REQ_DECOMPRESS = 1, 2
 
 
@@ -148,6 +148,8 @@ def lib():
         L.lcp_kernel_timer_read.argtypes = [P, C.POINTER(C.c_double), C.POINTER(C.c_uint64),
                                             C.POINTER(C.c_uint64)]
         L.lcp_scratch_bytes.argtypes = [C.POINTER(lcp_params), C.POINTER(C.c_uint64)]
+        L.lcp_compress_static.argtypes = [C.POINTER(lcp_params), C.c_uint64, P, P, C.c_uint64, P,
+                                          P, P]
         L.lcp_server_create.argtypes = [C.POINTER(lcp_server_params), C.POINTER(P)]
         L.lcp_server_destroy.argtypes = [P]
         L.lcp_server_destroy.restype = None
@@ -287,6 +289,39 @@ class Plan:
         _check(lib().lcp_kernel_timer_read(self.h, C.byref(ms), C.byref(la), C.byref(by)),
                "lcp_kernel_timer_read")
         return ms.value, la.value, by.value
+
+
+def compress_static(frames: Sequence, eb: float, eb_mode: int = EB_ABS, n_fields: int = 3,
+                    block_log2: int = 4, chunk_log2: int = 10, max_particles: int = 0,
+                    max_batch_particles: int = 0, max_batch_frames: int = 0, out=None,
+                    want_perm: bool = False, device: int = 0):
+    """lcp_compress_static: LCP-S records of independent frames on the library's
+    static scratch (no plan, no allocation inside the call).  Returns
+    (out uint8 tensor, offsets list, perms list|None)."""
+    import torch
+    nf = len(frames)
+    frames = [f if f.is_contiguous() else f.contiguous() for f in frames]
+    n_max = max(int(f.shape[1]) for f in frames)
+    p = lcp_params(eb_mode, eb, n_fields, 0, 0, block_log2, chunk_log2,
+                   max_particles or n_max, 0, device, max_batch_particles, max_batch_frames)
+    if out is None:
+        def bound(n):  # worst-case record bytes (what lcp_bound gives)
+            w = lambda bits: (bits + 31) // 32  # noqa: E731
+            return (80 + 8 * n_fields + 32 * (n_fields + 2) + 4 * w(63 * n) + 4 * w(33 * n)
+                    + 4 * n_fields * w(25 * n))
+        out = torch.empty(sum(bound(int(f.shape[1])) for f in frames), dtype=torch.uint8,
+                          device=frames[0].device)
+    fin, keep = frame_in_table(frames, n_fields)
+    offs = (C.c_uint64 * (nf + 1))()
+    perms = None
+    pp = None
+    if want_perm:
+        perms = [torch.empty(int(f.shape[1]), dtype=torch.int32, device=f.device) for f in frames]
+        pp = (C.c_void_p * nf)(*[t.data_ptr() for t in perms])
+    st = lib().lcp_compress_static(C.byref(p), nf, fin, out.data_ptr(), out.numel(), offs, pp,
+                                   torch.cuda.current_stream(device).cuda_stream)
+    _check(st, "lcp_compress_static")
+    return out, [int(v) for v in offs], perms
 
 
 def scratch_bytes(n_fields: int = 3, multi_frame: bool = True, max_particles: int = 1 << 20,

@@ -69,3 +69,26 @@ def test_descriptor_tables_match_field_by_field_filling():
     for j, o in enumerate(outs):
         assert [fo[j].fields[k] for k in range(F)] == [o[k].data_ptr() for k in range(F)]
         assert fo[j].capacity == o.shape[1]
+
+
+def test_static_entry_refuses_on_the_host():
+    """lcp_compress_static checks its parameters and whether the scratch they
+    need fits its static array before any HIP call, so the refusals show on a
+    machine without a GPU too."""
+    import ctypes as C
+    if not os.path.exists(lcp.LIB_PATH):
+        pytest.skip("library not built")
+    L = lcp.lib()
+
+    def call(n, multi=0, k=4, frames=0, F=3):
+        p = lcp.lcp_params(lcp.EB_ABS, 1e-3, F, multi, 0, k, 10, n, 0, 0, 0, frames)
+        offs = (C.c_uint64 * 2)()
+        return L.lcp_compress_static(C.byref(p), 0, None, None, 0, offs, None, None)
+
+    assert call(1 << 20) == lcp.ERR_BUDGET          # 2^20 particles need more than 64 MiB
+    assert call(553409) == lcp.ERR_BUDGET           # one past the three-field limit
+    assert call(436929, F=6) == lcp.ERR_BUDGET      # one past the six-field limit
+    assert call(1000, frames=64) == lcp.ERR_BUDGET  # 64 frames per launch set
+    assert call(1000, multi=1) == lcp.ERR_ARG       # LCP-S only
+    assert call(1000, k=-1) == lcp.ERR_ARG          # no block-size search
+    assert call(0) == lcp.ERR_ARG
