@@ -267,6 +267,24 @@ def bench_batched(args, torch, lcp, datagen, dev):
             lat_d.append(time.perf_counter() - t)
         return sum(lat_c), sum(lat_d), offs, lat_c, lat_d
 
+    # launch shape: the autotuner's choice for this batch, then the same calls
+    # with graphs switched off for comparison
+    tuned, tuned_ms, default_ms = bplan.autotune(frames, outb, reps=1)
+    log(f"autotune: {tuned}, {tuned_ms:.2f} ms per batch (defaults {default_ms:.2f} ms)")
+
+    def compress_ms(graphs, reps=3):
+        bplan.set_tuning(tuned["tile"], tuned["grid"], tuned["slot_grid"], graphs)
+        best = 1e30
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            bplan.compress(frames, out=outb)
+            best = min(best, time.perf_counter() - t)
+        return best * 1e3
+
+    ms_nograph = compress_ms(False)
+    ms_graph = compress_ms(True)
+    bplan.reset()  # frame sequence numbers start again, as the plain plan's do
     for _ in range(args.batched_warmup):
         batched()
         plain()
@@ -317,6 +335,9 @@ def bench_batched(args, torch, lcp, datagen, dev):
         "plain_decompress_call_ms_p50": pct(ld_all, 50),
         "plain_decompress_call_ms_p99": pct(ld_all, 99),
         "ratio": size_d / boffs[-1], "bytes_equal_plain": bool(same),
+        "launch_shape": {"autotuned": tuned, "autotune_best_ms": tuned_ms,
+                         "defaults_ms": default_ms,
+                         "compress_ms_graph": ms_graph, "compress_ms_no_graph": ms_nograph},
         "path_roofline": {"bound": "hbm",
                           "batched_compress": path_frac((size_d + boffs[-1]) * steps, bc),
                           "batched_decompress": path_frac((size_d + boffs[-1]) * steps, bd),

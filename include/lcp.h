@@ -202,8 +202,8 @@ const char* lcp_status_string(lcp_status status);
  * [0, 16] (no search); max_particles, max_batch_particles and max_batch_frames
  * (0 means 1 here: one frame per launch set) size the scratch the call needs,
  * which must fit the array -- else LCP_ERR_BUDGET before any HIP call.  With one
- * frame per launch set that is up to 553,408 particles of three fields (436,928
- * of six); each further frame per launch set costs about 2 MB.  The other
+ * frame per launch set that is a frame of about 550,000 particles of three
+ * fields (about 370,000 of six); each further frame per launch set costs about 2 MB.  The other
  * arguments and errors are lcp_compress's (methods are all LCP_METHOD_S).
  * Calls on one GPU share its array and keep none of each other's state: the
  * library runs them one at a time (each call has finished on the GPU when it
@@ -211,6 +211,46 @@ const char* lcp_status_string(lcp_status status);
 lcp_status lcp_compress_static(const lcp_params* params, uint64_t n_frames,
                                const lcp_frame_in* frames, void* out, uint64_t out_cap,
                                uint64_t* out_offsets, uint32_t* const* perms, hipStream_t stream);
+
+/* ---- Launch shape of batched LCP-S compression, and its autotuner ----
+ *
+ * How the kernels of a batch of independent frames are launched; never a
+ * format parameter (records are the same bytes under every setting).  tile:
+ * slots per tile of the element-wise encode kernels, a multiple of 256 in
+ * [256, 16384].  grid: persistent workgroups those kernels walk their tiles
+ * with (0: one workgroup per tile).  slot_grid: the same for the slot-symbol
+ * kernel (256-slot tiles).  graphs: 1 captures the kernels of each batch
+ * launch shape (frame sizes, output buffer) into a hipGraph on first use and
+ * replays it afterwards (plans created by lcp_plan only; at most 8 shapes are
+ * kept per plan). */
+typedef struct {
+  uint32_t tile;
+  uint32_t grid;
+  uint32_t slot_grid;
+  int graphs;
+} lcp_tuning;
+
+/* Set or read a plan's launch shape (LCP_ERR_ARG on an invalid setting).  A
+ * plan starts from the autotuner's cached choice for its device, particle
+ * count and fields if there is one (checked per call), else tile 1024, grid 0,
+ * slot_grid 0, graphs 1; an explicit setting overrides the cache. */
+lcp_status lcp_plan_set_tuning(lcp_plan_t plan, const lcp_tuning* tuning);
+lcp_status lcp_plan_get_tuning(lcp_plan_t plan, lcp_tuning* tuning);
+
+/* Autotuner: compresses the given frames (as lcp_compress on this single-frame
+ * plan would, into out) under each candidate launch shape -- tile 1024, 2048
+ * or 4096, grid 0, 8 or 32 workgroups per compute unit, slot_grid 0 or 16 per
+ * compute unit -- repeats best-of-reps timings of each on the stream, keeps
+ * the fastest for this plan and stores it in a process-wide cache keyed by
+ * (GPU name and compute units, bit width of the call's total particles,
+ * n_fields) that later calls of any plan consult.  The plan's stream state
+ * (frame sequence numbers) is left as it was.  *chosen (nullable) receives the
+ * choice, *best_ms and *default_ms (nullable) the time of one call under it
+ * and under the defaults.  Errors: those of lcp_compress; LCP_ERR_ARG for a
+ * multi-frame plan. */
+lcp_status lcp_plan_autotune(lcp_plan_t plan, uint64_t n_frames, const lcp_frame_in* frames,
+                             void* out, uint64_t out_cap, int reps, hipStream_t stream,
+                             lcp_tuning* chosen, double* best_ms, double* default_ms);
 
 /* Kernel timing for roofline measurement: while a name is set, one launch in
  * sixteen of the kernel with that name (the first, the 17th, ...) carries HIP

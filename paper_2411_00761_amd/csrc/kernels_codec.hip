@@ -1413,7 +1413,8 @@ __global__ __launch_bounds__(kThreads) void k_pack_wave(const EncArr* E, ArrWork
                                                         uint32_t* stage, uint32_t slot,
                                                         uint32_t* err, const uint32_t* hpart,
                                                         const unsigned long long* hmax,
-                                                        int build) {
+                                                        int build, uint32_t* err_rec,
+                                                        int err_stride) {
   extern __shared__ uint32_t bufs[];
   __shared__ uint32_t lc[kPackLcLds];
   __shared__ unsigned long long wsum[kPackWaves];
@@ -1488,7 +1489,7 @@ __global__ __launch_bounds__(kThreads) void k_pack_wave(const EncArr* E, ArrWork
       // the array is laid out as fixed length meanwhile (its fields within
       // its input) and the frame is coded again
       if (threadIdx.x == 0) {
-        atomicOr(err, kErrRebuild);
+        atomicOr(err_rec ? err_rec + (uint64_t)e.rec * err_stride : err, kErrRebuild);
         if (lb == 0) {
           w.U = 0;
           w.L = 0;
@@ -2552,7 +2553,7 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
     }
     launch_timed("pack_huff", L.values * 6ull, kernel, L.chunk_blocks, kThreads, shm, s, L.arrs,
                  work, pre_chunk, NA, chunk_log2, X.chunk_words, X.stage, slot32, err,
-                 X.hist_part, X.hist_max, fused);
+                 X.hist_part, X.hist_max, fused, L.err_rec, L.err_stride);
   } else {
     const size_t shm = (size_t)slot64 * 4;
     const uint32_t g = L.chunk_blocks;

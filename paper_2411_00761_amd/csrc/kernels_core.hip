@@ -364,6 +364,271 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
   }
 }
 
+// A run of J temporal frames that share one reference grid and slot order, each
+// coded against the frame before it (the first against q_ref), in one launch:
+// every thread owns fixed slots (four consecutive ones on the vector path, one
+// otherwise), keeps their codes in registers from frame to frame, and per frame
+// gathers the values through the permutation, quantises them on the grid,
+// writes the zigzag residuals as bytes (255: the value is in the escape array)
+// and counts them.  The workgroup keeps every frame's counts of symbols below
+// kRunPriv in LDS (larger symbols go straight to the spread copy), so the
+// frames follow one another without a barrier; the counts are merged into each
+// array's spread copy once at the end.  Only the last frame's codes are stored.
+// Array (frame j, field f) of the run is a = (a0 + j) F + f: its bytes at
+// v8 + a * astride, escapes at vesc + a * astride, histogram copies
+// [a copies, (a + 1) copies), work record zw[a]; frame j's error word at
+// err + j * err_stride.
+constexpr int kRunPriv = 128;
+template <int F>
+__global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, uint64_t n,
+                                                          GridDev g, const uint32_t* perm,
+                                                          const int32_t* q_ref, int32_t* q_last,
+                                                          uint8_t* v8, uint32_t* vesc,
+                                                          uint64_t astride, int a0,
+                                                          uint32_t* hist_part,
+                                                          unsigned long long* hist_max,
+                                                          int copies, ArrWork* zw, uint32_t* err,
+                                                          int err_stride, int vec) {
+  extern __shared__ uint32_t bins_lds[];  // [J][F][kRunPriv]
+  __shared__ uint32_t smax[kRunMax][F];
+  const int nbins = J * F * kRunPriv;
+  for (int j = threadIdx.x; j < nbins; j += kThreads) bins_lds[j] = 0;
+  if (threadIdx.x < (uint32_t)(kRunMax * F)) (&smax[0][0])[threadIdx.x] = 0;
+  // the coder's word totals of every array of the run start from zero
+  if (zw && blockIdx.x == 0)
+    for (int t = threadIdx.x; t < J * F * kWordParts; t += kThreads)
+      zw[(uint64_t)a0 * F + t / kWordParts].huff_words[t % kWordParts] = 0;
+  const int copy = blockIdx.x % copies;
+  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const uint64_t items = vec ? n / 4 : n;
+  const bool mine = gid < items;
+  // the thread's slots, their input indices and their running codes
+  uint32_t idx[4] = {0, 0, 0, 0};
+  int32_t q[F][4];
+  if (mine) {
+    if (vec) {
+      const uint4 iv = reinterpret_cast<const uint4*>(perm)[gid];
+      idx[0] = iv.x;
+      idx[1] = iv.y;
+      idx[2] = iv.z;
+      idx[3] = iv.w;
+    } else {
+      idx[0] = perm[gid];
+    }
+  }
+#pragma unroll
+  for (int f = 0; f < F; f++) {
+    q[f][0] = q[f][1] = q[f][2] = q[f][3] = 0;
+    if (mine) {
+      if (vec) {
+        const int4 qr = reinterpret_cast<const int4*>(q_ref + (uint64_t)f * n)[gid];
+        q[f][0] = qr.x;
+        q[f][1] = qr.y;
+        q[f][2] = qr.z;
+        q[f][3] = qr.w;
+      } else {
+        q[f][0] = q_ref[(uint64_t)f * n + gid];
+      }
+    }
+  }
+  __syncthreads();
+  for (int j = 0; j < J; j++) {
+    uint32_t bad = 0;
+#pragma unroll
+    for (int f = 0; f < F; f++) {
+      const uint64_t a = (uint64_t)(a0 + j) * F + f;
+      uint32_t* shared = hist_part + (a * copies + copy) * kAlphabet;
+      uint32_t* bins = bins_lds + (j * F + f) * kRunPriv;
+      const float* x = fr.x[j][f];
+      uint8_t* out8 = v8 + a * astride;
+      uint32_t* oesc = vesc + a * astride;
+      uint32_t rmax = 0;
+      if (vec) {
+        float xv[4];
+        if (mine) {
+#pragma unroll
+          for (int u = 0; u < 4; u++) xv[u] = x[idx[u]];
+        }
+        uint32_t rv[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          int64_t qn = 0;
+          if (mine) t_code(xv[u], g, f, &bad, &qn);
+          rv[u] = (uint32_t)zigzag64(qn - (int64_t)q[f][u]);
+          q[f][u] = (int32_t)qn;
+          if (mine) rmax = max(rmax, rv[u]);
+        }
+        if (mine) {
+          uint32_t bytes = 0;
+#pragma unroll
+          for (int u = 0; u < 4; u++) bytes |= min(rv[u], 255u) << (8 * u);
+          reinterpret_cast<uint32_t*>(out8)[gid] = bytes;
+#pragma unroll
+          for (int u = 0; u < 4; u++)
+            if (rv[u] >= 255u) oesc[4 * gid + u] = rv[u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          int e;
+          wave_hist_add(shared, bins, kRunPriv, (uint32_t)symbol_of(rv[u], &e), mine);
+        }
+      } else {
+        uint32_t r = 0;
+        if (mine) {
+          int64_t qn;
+          t_code(x[idx[0]], g, f, &bad, &qn);
+          r = (uint32_t)zigzag64(qn - (int64_t)q[f][0]);
+          q[f][0] = (int32_t)qn;
+          out8[gid] = (uint8_t)min(r, 255u);
+          if (r >= 255u) oesc[gid] = r;
+          rmax = r;
+        }
+        int e;
+        wave_hist_add(shared, bins, kRunPriv, (uint32_t)symbol_of(r, &e), mine);
+      }
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, d, kWave));
+      if (lane_id() == 0 && rmax) atomicMax(&smax[j][f], rmax);
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) bad |= (uint32_t)__shfl_xor((int)bad, d, kWave);
+    if (lane_id() == 0 && bad) atomicOr(err + (uint64_t)j * err_stride, bad);
+  }
+  if (mine && q_last) {
+#pragma unroll
+    for (int f = 0; f < F; f++) {
+      if (vec) reinterpret_cast<int4*>(q_last + (uint64_t)f * n)[gid] = make_int4(q[f][0], q[f][1], q[f][2], q[f][3]);
+      else q_last[(uint64_t)f * n + gid] = q[f][0];
+    }
+  }
+  __syncthreads();
+  // every frame's counts into its arrays' spread copies (non-zero bins)
+  for (int t = threadIdx.x; t < nbins; t += kThreads) {
+    const uint32_t c = bins_lds[t];
+    if (c) {
+      const uint64_t a = (uint64_t)a0 * F + t / kRunPriv;  // t / kRunPriv = j F + f
+      atomicAdd(&hist_part[(a * copies + copy) * kAlphabet + t % kRunPriv], c);
+    }
+  }
+  if (threadIdx.x < (uint32_t)(J * F)) {
+    const uint32_t m = (&smax[0][0])[threadIdx.x];
+    if (m) atomicMax(&hist_max[((uint64_t)a0 * F + threadIdx.x) * copies + copy], (unsigned long long)m);
+  }
+}
+
+// Temporal frames of several streams in one launch: workgroup b codes a tile
+// of 256 items (four slots each on a frame's vector path, one otherwise) of the
+// frame the prefix table gives it, exactly as k_t_resid codes a frame, its
+// counts merged into that frame's arrays' spread copies.
+__global__ __launch_bounds__(kThreads) void k_t_resid_multi(const TFrameDev* T, const uint32_t* pre,
+                                                            int R, int F, uint32_t* hist_part,
+                                                            unsigned long long* hist_max,
+                                                            int copies, ArrWork* zw) {
+  extern __shared__ uint32_t bins_lds[];
+  __shared__ uint32_t smax[kMaxF][kThreads / kWave];
+  auto bins = [&](int f, int w) { return bins_lds + ((uint32_t)f * (kThreads / kWave) + w) * kResPriv; };
+  for (int j = threadIdx.x; j < F * (kThreads / kWave) * kResPriv; j += kThreads) bins_lds[j] = 0;
+  const int r = seg_of_block(pre, R, blockIdx.x);
+  const TFrameDev& fr = T[r];
+  const uint32_t lb = blockIdx.x - pre[r];
+  if (zw && lb == 0 && threadIdx.x < (uint32_t)(F * kWordParts))
+    zw[(uint64_t)r * F + threadIdx.x / kWordParts].huff_words[threadIdx.x % kWordParts] = 0;
+  __syncthreads();
+  const int copy = lb % copies;
+  const uint64_t n = fr.n;
+  const uint64_t item = (uint64_t)lb * kThreads + threadIdx.x;
+  const bool mine = item < (fr.vec ? n / 4 : n);
+  uint32_t bad = 0;
+  uint32_t rmax[kMaxF];
+#pragma unroll
+  for (int f = 0; f < kMaxF; f++) rmax[f] = 0;
+  uint32_t idx[4] = {0, 0, 0, 0};
+  if (mine) {
+    if (fr.vec) {
+      const uint4 iv = reinterpret_cast<const uint4*>(fr.perm)[item];
+      idx[0] = iv.x;
+      idx[1] = iv.y;
+      idx[2] = iv.z;
+      idx[3] = iv.w;
+    } else {
+      idx[0] = fr.perm[item];
+    }
+  }
+  const int cnt = fr.vec ? 4 : 1;
+  for (int f = 0; f < F; f++) {
+    uint32_t* shared = hist_part + (((uint64_t)r * F + f) * copies + copy) * kAlphabet;
+    uint32_t rv[4] = {0, 0, 0, 0};
+    if (mine) {
+      const uint64_t s0 = fr.vec ? 4 * item : item;
+      for (int u = 0; u < cnt; u++) {
+        int64_t q;
+        t_code(fr.x[f][idx[u]], fr.g, f, &bad, &q);
+        rv[u] = (uint32_t)zigzag64(q - (int64_t)fr.q_ref[(uint64_t)f * n + s0 + u]);
+        fr.q_new[(uint64_t)f * n + s0 + u] = (int32_t)q;
+        fr.v8[(uint64_t)f * n + s0 + u] = (uint8_t)min(rv[u], 255u);
+        if (rv[u] >= 255u) fr.esc[(uint64_t)f * n + s0 + u] = rv[u];
+        rmax[f] = max(rmax[f], rv[u]);
+      }
+    }
+    for (int u = 0; u < 4; u++) {
+      int e;
+      wave_hist_add(shared, bins(f, wave_id()), kResPriv, (uint32_t)symbol_of(rv[u], &e),
+                    mine && u < cnt);
+    }
+  }
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) bad |= (uint32_t)__shfl_xor((int)bad, d, kWave);
+  if (lane_id() == 0 && bad) atomicOr(fr.err, bad);
+  for (int f = 0; f < F; f++) {
+    uint32_t m = rmax[f];
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, kWave));
+    if (lane_id() == 0) smax[f][wave_id()] = m;
+  }
+  __syncthreads();
+  for (int f = 0; f < F; f++) {
+    const uint64_t a = (uint64_t)r * F + f;
+    uint32_t* shared = hist_part + (a * copies + copy) * kAlphabet;
+    for (int j = threadIdx.x; j < kResPriv; j += kThreads) {
+      uint32_t t = 0;
+      for (int w = 0; w < kThreads / kWave; w++) t += bins(f, w)[j];
+      if (t) atomicAdd(&shared[j], t);
+    }
+    if (threadIdx.x == 0) {
+      uint32_t m = 0;
+      for (int w = 0; w < kThreads / kWave; w++) m = max(m, smax[f][w]);
+      if (m) atomicMax(&hist_max[a * copies + copy], (unsigned long long)m);
+    }
+  }
+}
+
+// Temporal frames of several streams reconstructed in one launch: workgroup b
+// takes 1024 slots of the frame the prefix table gives it.
+__global__ __launch_bounds__(kThreads) void k_t_recon_multi(const TReconDev* T, const uint32_t* pre,
+                                                            int R, int F, uint32_t* err) {
+  const int r = seg_of_block(pre, R, blockIdx.x);
+  const TReconDev& fr = T[r];
+  const uint64_t n = fr.n;
+  const uint64_t s0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg1k;
+  uint32_t bad = 0;
+  for (int f = 0; f < F; f++) {
+    for (uint32_t j = threadIdx.x; j < kSeg1k; j += kThreads) {
+      const uint64_t s = s0 + j;
+      if (s >= n) break;
+      int32_t rr = fr.r8[(uint64_t)f * n + s];
+      if (rr == -128) rr = reinterpret_cast<const int32_t*>(fr.out[f])[s];
+      int64_t q = (int64_t)fr.q_ref[(uint64_t)f * n + s] + rr;
+      if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
+        bad = 1;
+        q = 0;
+      }
+      fr.out[f][s] = reconstruct(q, fr.eb_q[f], fr.m[f]);
+      fr.q_new[(uint64_t)f * n + s] = (int32_t)q;
+    }
+  }
+  if (bad) atomicOr(err, kErrCorrupt);
+}
+
 // The codes a temporal frame leaves as the next frame's reference: the frame's
 // Eq. 5 codes on its reference grid, in the reference's slot order.  They
 // depend on the frame, the grid and the slot order only (not on the
@@ -474,21 +739,27 @@ __global__ __launch_bounds__(kThreads) void k_extent_final_b(const uint32_t* par
   }
 }
 
-// Eq. 5 and Eq. 6 per particle.  vals = index within the frame; prel = the
-// particle's three offsets inside its block (k <= 16 bits each), in input
-// order, so the slot pass gathers one word per slot instead of three floats.
+// Eq. 5 and Eq. 6 per particle.  vals = index within the frame.  rec holds,
+// per particle in input order, what the slot pass needs of it in one padded
+// record of rw words: the three offsets inside its block (k <= 16 bits each,
+// 16 bits apart, words 0-1) and the codes of the supplementary fields (words
+// 2..F-1), so the slot pass gathers one record per slot instead of F - 2
+// separate values.
+// Persistent over the batch's tiles of `tile` slots (tile t of frame r at
+// prefix pre[r]); every element-wise batch kernel below walks its tiles so.
 __global__ __launch_bounds__(kThreads) void k_quant_key_b(const SegDev* S, const uint32_t* pre,
-                                                          int R, uint64_t* keys, uint32_t* vals,
-                                                          uint64_t* prel) {
-  const int r = seg_of_block(pre, R, blockIdx.x);
+                                                          int R, int F, uint32_t tile,
+                                                          uint32_t tiles, uint64_t* keys,
+                                                          uint32_t* vals, uint32_t* rec, int rw) {
+  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+  const int r = seg_of_block(pre, R, t);
   const SegDev& g = S[r];
   const uint64_t n = g.n;
-  const uint64_t i0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg1k;
+  const uint64_t i0 = (uint64_t)(t - pre[r]) * tile;
   const int k = g.k;
   const uint64_t pm = (1ull << k) - 1ull;
-#pragma unroll
-  for (int j = 0; j < (int)(kSeg1k / kThreads); j++) {
-    const uint64_t i = i0 + (uint64_t)j * kThreads + threadIdx.x;
+  for (uint32_t j = threadIdx.x; j < tile; j += kThreads) {
+    const uint64_t i = i0 + j;
     if (i < n) {
       const uint64_t q0 = (uint64_t)quantise(g.x[0][i], g.m[0], g.inv[0]);
       const uint64_t q1 = (uint64_t)quantise(g.x[1][i], g.m[1], g.inv[1]);
@@ -496,8 +767,20 @@ __global__ __launch_bounds__(kThreads) void k_quant_key_b(const SegDev* S, const
       const uint64_t b0 = q0 >> k, b1 = q1 >> k, b2 = q2 >> k;
       keys[g.off + i] = b0 + g.bn0 * (b1 + g.bn1 * b2);  // Eq. 6, x fastest
       vals[g.off + i] = (uint32_t)i;
-      prel[g.off + i] = (q0 & pm) | ((q1 & pm) << 16) | ((q2 & pm) << 32);
+      const uint64_t pr = (q0 & pm) | ((q1 & pm) << 16) | ((q2 & pm) << 32);
+      uint32_t w[8] = {(uint32_t)pr, (uint32_t)(pr >> 32), 0, 0, 0, 0, 0, 0};
+#pragma unroll
+      for (int f = 3; f < kMaxF; f++)
+        if (f < F) w[f - 1] = (uint32_t)quantise(g.x[f][i], g.m[f], g.inv[f]);
+      uint32_t* d = rec + (g.off + i) * (uint64_t)rw;
+      if (rw == 2) {
+        *reinterpret_cast<uint2*>(d) = make_uint2(w[0], w[1]);
+      } else {
+        *reinterpret_cast<uint4*>(d) = make_uint4(w[0], w[1], w[2], w[3]);
+        if (rw == 8) *reinterpret_cast<uint4*>(d + 4) = make_uint4(w[4], w[5], w[6], w[7]);
+      }
     }
+  }
   }
 }
 
@@ -505,28 +788,31 @@ __global__ __launch_bounds__(kThreads) void k_quant_key_b(const SegDev* S, const
 // differs from the previous slot's.
 __global__ __launch_bounds__(kThreads) void k_run_flags_b(const uint64_t* keys, const SegDev* S,
                                                           const uint32_t* pre, int R,
+                                                          uint32_t tile, uint32_t tiles,
                                                           uint32_t* flags) {
-  const int r = seg_of_block(pre, R, blockIdx.x);
-  const uint64_t n = S[r].n, off = S[r].off;
-  const uint64_t i0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg1k;
-#pragma unroll
-  for (int j = 0; j < (int)(kSeg1k / kThreads); j++) {
-    const uint64_t i = i0 + (uint64_t)j * kThreads + threadIdx.x;
-    if (i < n) flags[off + i] = (i == 0 || keys[off + i] != keys[off + i - 1]) ? 1u : 0u;
+  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const int r = seg_of_block(pre, R, t);
+    const uint64_t n = S[r].n, off = S[r].off;
+    const uint64_t i0 = (uint64_t)(t - pre[r]) * tile;
+    for (uint32_t j = threadIdx.x; j < tile; j += kThreads) {
+      const uint64_t i = i0 + j;
+      if (i < n) flags[off + i] = (i == 0 || keys[off + i] != keys[off + i - 1]) ? 1u : 0u;
+    }
   }
 }
 
 __global__ __launch_bounds__(kThreads) void k_runs_write_b(const uint64_t* keys,
                                                            const uint32_t* scan, const SegDev* S,
                                                            const uint32_t* pre, int R,
+                                                           uint32_t tile, uint32_t tiles,
                                                            uint64_t* ids, uint32_t* starts,
                                                            uint32_t* rstart, uint32_t* Bs) {
-  const int r = seg_of_block(pre, R, blockIdx.x);
+  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+  const int r = seg_of_block(pre, R, t);
   const uint64_t n = S[r].n, off = S[r].off;
-  const uint64_t i0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg1k;
-#pragma unroll
-  for (int j = 0; j < (int)(kSeg1k / kThreads); j++) {
-    const uint64_t i = i0 + (uint64_t)j * kThreads + threadIdx.x;
+  const uint64_t i0 = (uint64_t)(t - pre[r]) * tile;
+  for (uint32_t j = threadIdx.x; j < tile; j += kThreads) {
+    const uint64_t i = i0 + j;
     if (i >= n) continue;
     const uint64_t g = off + i;
     if (i == 0 || keys[g] != keys[g - 1]) {
@@ -539,6 +825,7 @@ __global__ __launch_bounds__(kThreads) void k_runs_write_b(const uint64_t* keys,
       Bs[r] = scan[g] - (off ? scan[off - 1] : 0u);
       if (r == R - 1) rstart[R] = scan[g];
     }
+  }
   }
 }
 
@@ -570,36 +857,72 @@ __global__ __launch_bounds__(kThreads) void k_block_syms_b(const uint64_t* ids,
   }
 }
 
-// Slot-order symbols, 256 slots per workgroup; thread 0 also quantises the slot
-// before the workgroup's first so that every relative position has its
-// predecessor for the delta (mod p), which restarts at each frame's first slot.
+// Slot-order symbols, 256 slots per workgroup: each slot gathers its
+// particle's record (offsets inside the block, supplementary codes); thread 0
+// also reads the offsets of the slot before the workgroup's first, so that
+// every relative position has its predecessor for the delta (mod p), which
+// restarts at each frame's first slot.  q_slot (nullable) receives the codes in
+// slot order: corner of the slot's block (from its sorted key) plus offset for
+// x, y, z, the record's codes for the other fields.
+__device__ inline void load_rec(const uint32_t* rec, uint64_t i, int rw, uint32_t* w) {
+  const uint32_t* p = rec + i * (uint64_t)rw;
+  if (rw == 2) {
+    const uint2 a = *reinterpret_cast<const uint2*>(p);
+    w[0] = a.x;
+    w[1] = a.y;
+  } else {
+    const uint4 a = *reinterpret_cast<const uint4*>(p);
+    w[0] = a.x;
+    w[1] = a.y;
+    w[2] = a.z;
+    w[3] = a.w;
+    if (rw == 8) {
+      const uint4 b = *reinterpret_cast<const uint4*>(p + 4);
+      w[4] = b.x;
+      w[5] = b.y;
+      w[6] = b.z;
+      w[7] = b.w;
+    }
+  }
+}
+
 __global__ __launch_bounds__(kThreads) void k_slot_syms_b(const SegDev* S, const uint32_t* pre,
                                                           int R, int F, const uint32_t* perm,
-                                                          const uint64_t* prel, uint64_t ntot,
-                                                          uint32_t* v_rel, uint32_t* v_sup,
-                                                          int32_t* q_slot) {
+                                                          const uint64_t* keys,
+                                                          const uint32_t* rec, int rw,
+                                                          uint64_t ntot, uint32_t* v_rel,
+                                                          uint32_t* v_sup, int32_t* q_slot,
+                                                          uint32_t tiles) {
   __shared__ uint32_t rel[3][kThreads + 1];
-  const int r = seg_of_block(pre, R, blockIdx.x);
+  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+  const int r = seg_of_block(pre, R, t);
   const SegDev& g = S[r];
   const uint64_t n = g.n, off = g.off;
-  const uint64_t s0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg256;
+  const uint64_t s0 = (uint64_t)(t - pre[r]) * kSeg256;
   const uint64_t s = s0 + threadIdx.x;
   const bool valid = s < n;
-  const uint32_t i = valid ? perm[off + s] : 0;
   if (valid) {
-    const uint64_t pr = prel[off + i];
+    const uint32_t i = perm[off + s];
+    uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    load_rec(rec, off + i, rw, w);
+    const uint64_t pr = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
     for (int d = 0; d < 3; d++) rel[d][threadIdx.x + 1] = (uint32_t)(pr >> (16 * d)) & 0xFFFFu;
-    for (int f = q_slot ? 0 : 3; f < F; f++) {
-      int64_t q = quantise(g.x[f][i], g.m[f], g.inv[f]);
-      if (f >= 3) v_sup[(uint64_t)(f - 3) * ntot + off + s] = (uint32_t)q;
-      if (q_slot) q_slot[(uint64_t)f * ntot + off + s] = (int32_t)q;
+    for (int f = 3; f < F; f++) v_sup[(uint64_t)(f - 3) * ntot + off + s] = w[f - 1];
+    if (q_slot) {
+      const uint64_t key = keys[off + s];
+      const uint64_t bx = key % g.bn0, rest = key / g.bn0;
+      const uint64_t b3[3] = {bx, rest % g.bn1, rest / g.bn1};
+      for (int d = 0; d < 3; d++)
+        q_slot[(uint64_t)d * ntot + off + s] = (int32_t)((b3[d] << g.k) + rel[d][threadIdx.x + 1]);
+      for (int f = 3; f < F; f++) q_slot[(uint64_t)f * ntot + off + s] = (int32_t)w[f - 1];
     }
   }
   if (threadIdx.x == 0) {
     if (s0 == 0) {
       rel[0][0] = rel[1][0] = rel[2][0] = 0;
     } else {
-      const uint64_t pr = prel[off + perm[off + s0 - 1]];
+      const uint64_t j = off + perm[off + s0 - 1];
+      const uint64_t pr = (uint64_t)rec[j * rw] | ((uint64_t)rec[j * rw + 1] << 32);
       for (int d = 0; d < 3; d++) rel[d][0] = (uint32_t)(pr >> (16 * d)) & 0xFFFFu;
     }
   }
@@ -608,20 +931,24 @@ __global__ __launch_bounds__(kThreads) void k_slot_syms_b(const SegDev* S, const
   if (valid)
     for (int d = 0; d < 3; d++)
       v_rel[(uint64_t)d * ntot + off + s] = (rel[d][threadIdx.x + 1] - rel[d][threadIdx.x]) & pm;
+  __syncthreads();  // the next tile reuses rel
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_copy_perm_b(const uint32_t* perm, const SegDev* S,
                                                           const uint32_t* pre, int R,
+                                                          uint32_t tile, uint32_t tiles,
                                                           uint32_t* const* dst) {
-  const int r = seg_of_block(pre, R, blockIdx.x);
-  uint32_t* d = dst[r];
-  if (!d) return;
-  const uint64_t n = S[r].n, off = S[r].off;
-  const uint64_t i0 = (uint64_t)(blockIdx.x - pre[r]) * kSeg1k;
-#pragma unroll
-  for (int j = 0; j < (int)(kSeg1k / kThreads); j++) {
-    const uint64_t i = i0 + (uint64_t)j * kThreads + threadIdx.x;
-    if (i < n) d[i] = perm[off + i];
+  for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+    const int r = seg_of_block(pre, R, t);
+    uint32_t* d = dst[r];
+    if (!d) continue;
+    const uint64_t n = S[r].n, off = S[r].off;
+    const uint64_t i0 = (uint64_t)(t - pre[r]) * tile;
+    for (uint32_t j = threadIdx.x; j < tile; j += kThreads) {
+      const uint64_t i = i0 + j;
+      if (i < n) d[i] = perm[off + i];
+    }
   }
 }
 
@@ -993,19 +1320,30 @@ void launch_extent_b(const SegDev* S, const uint32_t* pre_ext, uint32_t ext_bloc
   k_extent_final_b<<<dim3(R, F), kThreads, 0, s>>>(part, pre_ext, R, F, ext_blocks, ext);
 }
 
-void launch_quant_key_b(const SegDev* S, const uint32_t* pre_1k, uint32_t blocks, int R,
-                        uint64_t* keys, uint32_t* vals, uint64_t* prel, uint64_t ntot,
-                        hipStream_t s) {
-  launch_timed("quant_key", ntot * (12 + 20), k_quant_key_b, blocks, kThreads, 0, s,
-               S, pre_1k, R, keys, vals, prel);
+int slot_rec_words(int F) { return F == 3 ? 2 : (F <= 5 ? 4 : 8); }
+
+inline uint32_t persistent_grid(uint32_t tiles, uint32_t grid) {
+  return grid && grid < tiles ? grid : (tiles ? tiles : 1);
 }
 
-void launch_runs_b(const uint64_t* keys, const SegDev* S, const uint32_t* pre_1k, uint32_t blocks,
-                   int R, uint64_t ntot, uint32_t* flags_scan, uint64_t* ids, uint32_t* starts,
-                   uint32_t* rstart, uint32_t* Bs, uint32_t* tmp32, hipStream_t s) {
-  k_run_flags_b<<<blocks, kThreads, 0, s>>>(keys, S, pre_1k, R, flags_scan);
+void launch_quant_key_b(const SegDev* S, const uint32_t* pre_tile, const TileShape& ts, int R,
+                        int F, uint64_t* keys, uint32_t* vals, uint32_t* rec, uint64_t ntot,
+                        hipStream_t s) {
+  const int rw = slot_rec_words(F);
+  launch_timed("quant_key", ntot * (4ull * F + 12 + 4ull * rw), k_quant_key_b,
+               persistent_grid(ts.tiles, ts.grid), kThreads, 0, s, S, pre_tile, R, F, ts.tile,
+               ts.tiles, keys, vals, rec, rw);
+}
+
+void launch_runs_b(const uint64_t* keys, const SegDev* S, const uint32_t* pre_tile,
+                   const TileShape& ts, int R, uint64_t ntot, uint32_t* flags_scan, uint64_t* ids,
+                   uint32_t* starts, uint32_t* rstart, uint32_t* Bs, uint32_t* tmp32,
+                   hipStream_t s) {
+  const uint32_t g = persistent_grid(ts.tiles, ts.grid);
+  k_run_flags_b<<<g, kThreads, 0, s>>>(keys, S, pre_tile, R, ts.tile, ts.tiles, flags_scan);
   scan_device<uint32_t>(flags_scan, ntot, nullptr, false, tmp32, s);
-  k_runs_write_b<<<blocks, kThreads, 0, s>>>(keys, flags_scan, S, pre_1k, R, ids, starts, rstart, Bs);
+  k_runs_write_b<<<g, kThreads, 0, s>>>(keys, flags_scan, S, pre_tile, R, ts.tile, ts.tiles, ids,
+                                        starts, rstart, Bs);
 }
 
 void launch_block_syms_b(const uint64_t* ids, const uint32_t* starts, const uint32_t* rstart,
@@ -1015,18 +1353,23 @@ void launch_block_syms_b(const uint64_t* ids, const uint32_t* starts, const uint
       ids, starts, rstart, R, S, ntot, v_id, v_cnt);
 }
 
-void launch_slot_syms_b(const SegDev* S, const uint32_t* pre_256, uint32_t blocks, int R, int F,
-                        const uint32_t* perm, const uint64_t* prel, uint64_t ntot, uint32_t* v_rel,
-                        uint32_t* v_sup, int32_t* q_slot, hipStream_t s) {
-  uint64_t bytes = ntot * (4 + 8 + 4ull * (F - 3) + 4ull * F + (q_slot ? 16ull * F : 0));
-  launch_timed("slot_syms", bytes, k_slot_syms_b, blocks, kThreads, 0, s,
-               S, pre_256, R, F, perm, prel, ntot, v_rel, v_sup, q_slot);
+void launch_slot_syms_b(const SegDev* S, const uint32_t* pre_256, uint32_t tiles, uint32_t grid,
+                        int R, int F, const uint32_t* perm, const uint64_t* keys,
+                        const uint32_t* rec, uint64_t ntot, uint32_t* v_rel, uint32_t* v_sup,
+                        int32_t* q_slot, hipStream_t s) {
+  const int rw = slot_rec_words(F);
+  uint64_t bytes = ntot * (4 + 4ull * rw + 4ull * F + (q_slot ? 8 + 4ull * F : 0));
+  launch_timed("slot_syms", bytes, k_slot_syms_b, persistent_grid(tiles, grid), kThreads, 0, s,
+               S, pre_256, R, F, perm, keys, rec, rw, ntot, v_rel, v_sup, q_slot, tiles);
 }
 
-void launch_copy_perm_b(const uint32_t* perm, const SegDev* S, const uint32_t* pre_1k,
-                        uint32_t blocks, int R, uint32_t* const* dst, hipStream_t s) {
-  k_copy_perm_b<<<blocks, kThreads, 0, s>>>(perm, S, pre_1k, R, dst);
+void launch_copy_perm_b(const uint32_t* perm, const SegDev* S, const uint32_t* pre_tile,
+                        const TileShape& ts, int R, uint32_t* const* dst, hipStream_t s) {
+  k_copy_perm_b<<<persistent_grid(ts.tiles, ts.grid), kThreads, 0, s>>>(perm, S, pre_tile, R,
+                                                                          ts.tile, ts.tiles, dst);
 }
+
+int radix_result(int bits) { return ((bits + 7) / 8) & 1; }
 
 int radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, const SegDev* S,
                const uint32_t* pre_tile, uint32_t ntiles, int R, uint64_t ntot, int bits,
@@ -1142,6 +1485,54 @@ void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
   launch_timed("t_resid", n * (4 + 12ull * F), k_t_resid, grid_for(vec ? n / 4 : n, kThreads, 4096), kThreads, (size_t)F * (kThreads / kWave) * kResPriv * 4, s,
                x, F, n, g, perm_ref, q_ref, v8, v_res, q_new, err, vec, hist_part, hist_max,
                zero_words);
+}
+
+void launch_t_resid_run(const RunFrames& fr, int J, int F, uint64_t n, const GridDev& g,
+                        const uint32_t* perm, const int32_t* q_ref, int32_t* q_last, uint8_t* v8,
+                        uint32_t* vesc, uint64_t astride, int a0, uint32_t* hist_part,
+                        unsigned long long* hist_max, int copies, ArrWork* zero_words,
+                        uint32_t* err, int err_stride, hipStream_t s) {
+  if (J < 1 || n == 0) return;
+  int vec = (n % 4 == 0) && al16(perm) && al16(q_ref) && (!q_last || al16(q_last)) &&
+            (astride % 16 == 0) && al16(v8);
+  const uint64_t items = vec ? n / 4 : n;
+  // algorithmic bytes of the run: the J frames read and their residual bytes
+  // written; the permutation and the first reference codes read, the last
+  // codes written, once for the run
+  auto* kernel = k_t_resid_run<3>;
+  switch (F) {
+    case 4: kernel = k_t_resid_run<4>; break;
+    case 5: kernel = k_t_resid_run<5>; break;
+    case 6: kernel = k_t_resid_run<6>; break;
+    case 7: kernel = k_t_resid_run<7>; break;
+    case 8: kernel = k_t_resid_run<8>; break;
+    default: break;
+  }
+  launch_timed("t_resid", n * ((uint64_t)J * 5 * F + 4 + 8ull * F), kernel,
+               grid_for(items, kThreads, 1u << 24), kThreads,
+               (size_t)J * F * kRunPriv * 4, s, fr, J, n, g, perm, q_ref,
+               q_last, v8, vesc, astride, a0, hist_part, hist_max, copies, zero_words, err,
+               err_stride, vec);
+}
+
+uint32_t t_multi_blocks(uint64_t n, int vec) {
+  const uint64_t items = vec ? n / 4 : n;
+  return (uint32_t)((items + kThreads - 1) / kThreads);
+}
+
+void launch_t_resid_multi(const TFrameDev* frames, const uint32_t* pre, uint32_t blocks, int R,
+                          int F, uint32_t* hist_part, unsigned long long* hist_max, int copies,
+                          ArrWork* zero_words, uint64_t bytes, hipStream_t s) {
+  if (!blocks) return;
+  launch_timed("t_resid", bytes, k_t_resid_multi, blocks, kThreads,
+               (size_t)F * (kThreads / kWave) * kResPriv * 4, s, frames, pre, R, F, hist_part,
+               hist_max, copies, zero_words);
+}
+
+void launch_t_recon_multi(const TReconDev* frames, const uint32_t* pre, uint32_t blocks, int R,
+                          int F, uint32_t* err, uint64_t bytes, hipStream_t s) {
+  if (!blocks) return;
+  launch_timed("t_recon", bytes, k_t_recon_multi, blocks, kThreads, 0, s, frames, pre, R, F, err);
 }
 
 void launch_t_codes(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,

@@ -6,9 +6,13 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <chrono>
 #include <initializer_list>
 #include <algorithm>
+#include <map>
 #include <mutex>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/lcp.h"
@@ -124,10 +128,20 @@ struct lcp_plan_s {
   // scratch laid out for LCP-S compression only (no decode tables): the
   // library's static scratch, which must stay small
   bool compress_only = false;
+  // scratch of a server's merged temporal launches: up to RB frames of
+  // different streams, NB particles in all (residual bytes, escapes, coder,
+  // decoder and frame tables; no spatial buffers)
+  bool serve_batch = false;
+  TFrameDev *tfr_host = nullptr, *tfr_dev = nullptr;
+  TReconDev *trc_host = nullptr, *trc_dev = nullptr;
+  uint32_t *spre_host = nullptr, *spre_dev = nullptr;        // [RB + 1] workgroup prefix
+  unsigned long long *sret_host = nullptr, *sret_dev = nullptr;  // [RB] errs, [RB + 1] offsets, launch err
+  uint64_t *sdst_host = nullptr, *sdst_dev = nullptr;        // [RB] (destination, capacity)
   size_t scratch_bytes = 0, host_bytes = 0, state_bytes = 0;
 
   // scratch (batch-wide arrays hold NB slots)
-  uint64_t *keys0, *keys1, *ids, *v_id, *v_cnt, *prel;
+  uint64_t *keys0, *keys1, *ids, *v_id, *v_cnt;
+  uint32_t* slot_rec;  // per particle: in-block offsets and supplementary codes
   uint32_t *vals0, *vals1, *hist, *flags, *starts, *v_slot, *chunk_words, *lut, *corner;
   uint8_t* v_byte;  // temporal residuals as bytes (multi-frame plans; escapes in v_slot)
   int8_t* dres8;    // decoded temporal residuals as bytes, kDecSlots frames (multi-frame)
@@ -145,8 +159,15 @@ struct lcp_plan_s {
   // whose residual alphabet outgrew the packing kernel's own build
   int fuse_skip = 0;
   // temporal runs (frames coded back to back, one read-back per run): per
-  // frame [4k] error word, [4k + 1, 4k + 3) record start and end
+  // frame [4k] error word; then the records' offsets (kTRun + 1) and the run's
+  // own error word
   unsigned long long *run_dev, *run_host;
+  // frames one run codes at once (0: no runs) and their buffers: residual
+  // bytes and escaped residuals of [run_max][F] arrays of run_stride values
+  int run_max = 0;
+  uint64_t run_stride = 0;
+  uint8_t* run_v8 = nullptr;
+  uint32_t* run_esc = nullptr;
   uint8_t* rec_tmp;  // second record (temporal candidate)
   uint64_t rec_tmp_cap;
   uint32_t* ext_part;    // extent partials
@@ -194,6 +215,16 @@ struct lcp_plan_s {
   uint64_t last_s = 0;
   bool have_last_s = false;
 
+  // launch shape of the batch encode kernels (tuned, or the defaults) and the
+  // graphs captured for batches of LCP-S frames, keyed by their launch shape
+  lcp_tuning tune{1024, 0, 0, 1};
+  bool tune_set = false;  // set by lcp_plan_autotune / lcp_plan_set_tuning
+  std::string dev_key;    // GPU name and compute units, for the tuning cache
+  std::vector<std::pair<std::vector<uint64_t>, hipGraphExec_t>> graphs;
+  hipStream_t cap_stream = nullptr;
+  bool capturing = false;  // kernels are being captured: no timer events
+  uint64_t graph_launches = 0, graph_captures = 0;
+
   // kernel timer
   char timer_name[64] = {0};
   std::vector<hipEvent_t> ev_free;
@@ -225,6 +256,11 @@ lcp_status hip_fail(hipError_t e, const char* what, int line) {
     hipError_t e_ = (x);                                       \
     if (e_ != hipSuccess) return hip_fail(e_, #x, __LINE__);   \
   } while (0)
+
+void drop_graphs(lcp_plan_s* P) {
+  for (auto& e : P->graphs) (void)hipGraphExecDestroy(e.second);
+  P->graphs.clear();
+}
 
 // Host table -> device: small tables through kernel arguments (a copy-engine
 // transfer costs tens of microseconds on the stream), large ones by copy from
@@ -344,7 +380,7 @@ lcp_status upload_segs(lcp_plan_s* P, int R, SegLayout* L, hipStream_t s) {
     p2[r] = l.blocks_256;
     pt[r] = l.tiles;
     l.ext_blocks += seg_ext_blocks(g.n);
-    l.blocks_1k += (uint32_t)((g.n + kSeg1k - 1) / kSeg1k);
+    l.blocks_1k += (uint32_t)((g.n + P->tune.tile - 1) / P->tune.tile);
     l.blocks_256 += (uint32_t)((g.n + kSeg256 - 1) / kSeg256);
     l.tiles += (uint32_t)((g.n + kSortTile - 1) / kSortTile);
   }
@@ -449,11 +485,9 @@ lcp_status enc_add(lcp_plan_s* P, EncBuild& B, const ArrIn& in, uint64_t nb, int
   return LCP_OK;
 }
 
-// Errors go to err and record offsets to offs (the plan's return block unless
-// given); with base (device) the first record starts at *base.
-lcp_status enc_launch(lcp_plan_s* P, EncBuild& B, uint8_t* out, uint64_t cap, bool hist_done,
-                      hipStream_t s, uint32_t* err = nullptr, unsigned long long* offs = nullptr,
-                      const unsigned long long* base = nullptr) {
+// The host side of an encode launch set: prefix tables, and the record, array
+// and prefix tables uploaded on stream s unless the device already holds them.
+lcp_status enc_prepare(lcp_plan_s* P, EncBuild& B, EncLaunch* Lo, hipStream_t s) {
   const int NA = B.NA;
   EncLaunch L;
   L.arrs = P->earr_dev;
@@ -487,6 +521,8 @@ lcp_status enc_launch(lcp_plan_s* P, EncBuild& B, uint8_t* out, uint64_t cap, bo
   L.values = B.values;
   L.all_bytes = 1;
   L.fused = B.fused ? 1 : 0;
+  L.err_rec = nullptr;
+  L.err_stride = 0;
   for (int a = 0; a < NA; a++) L.all_bytes &= P->earr_host[a].in.esc != nullptr ? 1 : 0;
   // A single record travels to the layout kernel as an argument; the array and
   // prefix tables are not uploaded again while the device holds the same bytes
@@ -513,6 +549,16 @@ lcp_status enc_launch(lcp_plan_s* P, EncBuild& B, uint8_t* out, uint64_t cap, bo
     memcpy(P->enc_cache.data() + arr_bytes, P->epre_host, pre_bytes);
     P->enc_cache_ok = true;
   }
+  *Lo = L;
+  return LCP_OK;
+}
+
+// The kernels of an encode launch set (tables in place).  Errors go to err and
+// record offsets to offs (the plan's return block unless given); with base
+// (device) the first record starts at *base.
+void enc_enqueue(lcp_plan_s* P, const EncLaunch& L, uint8_t* out, uint64_t cap, bool hist_done,
+                 hipStream_t s, uint32_t* err = nullptr, unsigned long long* offs = nullptr,
+                 const unsigned long long* base = nullptr) {
   EncScratch X;
   X.chunk_words = P->chunk_words;
   X.stage = P->stage;
@@ -522,6 +568,18 @@ lcp_status enc_launch(lcp_plan_s* P, EncBuild& B, uint8_t* out, uint64_t cap, bo
   X.huff_maxd = P->huff_maxd;
   launch_encode(L, P->chunk_log2, P->work, X, out, cap, offs ? offs : P->offs_dev,
                 err ? err : P->err, base, hist_done, s);
+}
+
+lcp_status enc_launch(lcp_plan_s* P, EncBuild& B, uint8_t* out, uint64_t cap, bool hist_done,
+                      hipStream_t s, uint32_t* err = nullptr, unsigned long long* offs = nullptr,
+                      const unsigned long long* base = nullptr, uint32_t* err_rec = nullptr,
+                      int err_stride = 0) {
+  EncLaunch L;
+  lcp_status st = enc_prepare(P, B, &L, s);
+  if (st) return st;
+  L.err_rec = err_rec;
+  L.err_stride = err_stride;
+  enc_enqueue(P, L, out, cap, hist_done, s, err, offs, base);
   return LCP_OK;
 }
 
@@ -558,7 +616,28 @@ RecHdr make_hdr(int mode, int F, int k, int cl, int A, uint64_t n, uint64_t seq,
   return h;
 }
 
-// ------------------------------------------------------------------ LCP-S
+// ------------------------------------------------------------------ graphs
+// The kernels of one launch shape, captured on the plan's own stream into a
+// graph (a fill kernel clears the error word first; no copies or memsets are
+// recorded) and instantiated.
+constexpr size_t kMaxGraphs = 8;
+template <typename K>
+lcp_status capture_graph(lcp_plan_s* P, K& kernels, hipGraphExec_t* exec) {
+  if (!P->cap_stream) HIP_OK(hipStreamCreateWithFlags(&P->cap_stream, hipStreamNonBlocking));
+  HIP_OK(hipStreamBeginCapture(P->cap_stream, hipStreamCaptureModeThreadLocal));
+  P->capturing = true;
+  launch_fill_u32(P->err, 1, 0u, P->cap_stream);
+  kernels(P->cap_stream);
+  P->capturing = false;
+  hipGraph_t graph = nullptr;
+  HIP_OK(hipStreamEndCapture(P->cap_stream, &graph));
+  const hipError_t e = hipGraphInstantiate(exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate", __LINE__);
+  P->graph_captures++;
+  return LCP_OK;
+}
+
 // LCP-S on R independent frames (seg_host[r].x / .n) in one set of launches.
 // g[r] are frame r's grids, hi[r] its maxima.  Records go back to back to out;
 // offs (host, R + 1) receives their offsets.  q_slot (R == 1 only) receives
@@ -597,27 +676,14 @@ lcp_status compress_s_batch(lcp_plan_s* P, int R, const HostGrid (*g)[kMaxF],
   }
   int sort_bits = 0;
   for (int r = 0; r < R; r++) sort_bits = kb[r] > sort_bits ? kb[r] : sort_bits;
+  // host side first: frame tables, encoder tables, permutation destinations,
+  // all uploaded on s; then the kernels, which read only device tables
   SegLayout L;
   lcp_status st = upload_segs(P, R, &L, s);
   if (st) return st;
   const uint64_t ntot = L.ntot;
-  const uint32_t* pre_1k = P->segpre_dev + (R + 1);
-  const uint32_t* pre_256 = P->segpre_dev + 2 * (R + 1);
-  launch_quant_key_b(P->seg_dev, pre_1k, L.blocks_1k, R, P->keys0, P->vals0, P->prel, ntot, s);
-  uint32_t* tmp32 = reinterpret_cast<uint32_t*>(P->scan_tmp);
-  const int cur = radix_sort(P->keys0, P->vals0, P->keys1, P->vals1, P->seg_dev,
-                             P->segpre_dev + 3 * (R + 1), L.tiles, R, ntot, sort_bits, P->hist,
-                             tmp32, s);
-  const uint64_t* keys = cur ? P->keys1 : P->keys0;
-  const uint32_t* perm = cur ? P->vals1 : P->vals0;
-  launch_runs_b(keys, P->seg_dev, pre_1k, L.blocks_1k, R, ntot, P->flags, P->ids, P->starts,
-                P->rstart, P->Bs, tmp32, s);
-  launch_block_syms_b(P->ids, P->starts, P->rstart, R, P->seg_dev, ntot, P->v_id, P->v_cnt, s);
   uint32_t* v_rel = P->v_slot;
   uint32_t* v_sup = P->v_slot + 3 * ntot;
-  launch_slot_syms_b(P->seg_dev, pre_256, L.blocks_256, R, F, perm, P->prel, ntot, v_rel, v_sup,
-                     q_slot, s);
-
   EncBuild B;
   B.R = R;
   for (int r = 0; r < R; r++) {
@@ -637,18 +703,64 @@ lcp_status compress_s_batch(lcp_plan_s* P, int R, const HostGrid (*g)[kMaxF],
       if ((st = enc_add(P, B, ArrIn{v_sup + (uint64_t)(f - 3) * ntot + o, 0, nullptr, n}, n, r, -1, 0)))
         return st;
   }
-  clear_err(P, s);
-  if ((st = enc_launch(P, B, out, cap, false, s))) return st;
+  EncLaunch EL;
+  if ((st = enc_prepare(P, B, &EL, s))) return st;
+  bool perm_copy = false;
   if (perm_dst) {
-    bool any = false;
     for (int r = 0; r < R; r++) {
       P->permdst_host[r] = perm_dst[r];
-      any |= perm_dst[r] != nullptr;
+      perm_copy |= perm_dst[r] != nullptr;
     }
-    if (any) {
-      if ((st = upload(P->permdst_host, P->permdst_dev, sizeof(uint32_t*) * R, s))) return st;
-      launch_copy_perm_b(perm, P->seg_dev, pre_1k, L.blocks_1k, R, P->permdst_dev, s);
+    if (perm_copy && (st = upload(P->permdst_host, P->permdst_dev, sizeof(uint32_t*) * R, s)))
+      return st;
+  }
+  // the sort leaves keys and permutation in one of two buffers, fixed by the
+  // number of 8-bit passes
+  const int cur = radix_result(sort_bits);
+  const uint64_t* keys = cur ? P->keys1 : P->keys0;
+  const uint32_t* perm = cur ? P->vals1 : P->vals0;
+  const uint32_t* pre_tile = P->segpre_dev + (R + 1);
+  const uint32_t* pre_256 = P->segpre_dev + 2 * (R + 1);
+  const TileShape ts{P->tune.tile, L.blocks_1k, P->tune.grid};
+  auto kernels = [&](hipStream_t q) {
+    launch_quant_key_b(P->seg_dev, pre_tile, ts, R, F, P->keys0, P->vals0, P->slot_rec, ntot, q);
+    uint32_t* tmp32 = reinterpret_cast<uint32_t*>(P->scan_tmp);
+    radix_sort(P->keys0, P->vals0, P->keys1, P->vals1, P->seg_dev, P->segpre_dev + 3 * (R + 1),
+               L.tiles, R, ntot, sort_bits, P->hist, tmp32, q);
+    launch_runs_b(keys, P->seg_dev, pre_tile, ts, R, ntot, P->flags, P->ids, P->starts, P->rstart,
+                  P->Bs, tmp32, q);
+    launch_block_syms_b(P->ids, P->starts, P->rstart, R, P->seg_dev, ntot, P->v_id, P->v_cnt, q);
+    launch_slot_syms_b(P->seg_dev, pre_256, L.blocks_256, P->tune.slot_grid, R, F, perm, keys,
+                       P->slot_rec, ntot, v_rel, v_sup, q_slot, q);
+    enc_enqueue(P, EL, out, cap, false, q);
+    if (perm_copy) launch_copy_perm_b(perm, P->seg_dev, pre_tile, ts, R, P->permdst_dev, q);
+  };
+  // A batch of frames from a plan that owns its scratch replays the graph of
+  // its launch shape (captured on first use); everything that differs between
+  // batches of one shape is in the tables uploaded above.
+  const bool graph = P->tune.graphs && R >= 2 && P->own_dev && !q_slot;
+  if (graph) {
+    std::vector<uint64_t> key = {(uint64_t)R, (uint64_t)F, (uint64_t)P->chunk_log2,
+                                 (uint64_t)sort_bits, P->tune.tile, P->tune.grid,
+                                 P->tune.slot_grid, (uint64_t)(uintptr_t)out, cap, perm_copy};
+    for (int r = 0; r < R; r++) key.push_back(P->seg_host[r].n);
+    hipGraphExec_t exec = nullptr;
+    for (auto& e : P->graphs)
+      if (e.first == key) exec = e.second;
+    if (!exec) {
+      if ((st = capture_graph(P, kernels, &exec))) return st;
+      if (P->graphs.size() >= kMaxGraphs) {
+        (void)hipGraphExecDestroy(P->graphs.front().second);
+        P->graphs.erase(P->graphs.begin());
+      }
+      P->graphs.push_back({key, exec});
     }
+    HIP_OK(hipGraphLaunch(exec, s));
+    P->graph_launches++;
+    P->err_clean = false;
+  } else {
+    clear_err(P, s);
+    kernels(s);
   }
   if (perm_res) *perm_res = perm;
   return finish_records(P, R, offs, nullptr, s);
@@ -981,6 +1093,7 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
 struct RunFrame {
   RefState ref;  // reference the frame is coded against
   int q;         // q slot of its codes
+  bool chain;    // the reference is the run frame just before (same grid and slot order)
 };
 
 // Frames that would be coded as T in a row if each of them stays T.
@@ -995,7 +1108,9 @@ int plan_run(const lcp_plan_s* P, const lcp_frame_in* fr, uint64_t nf, uint64_t 
   RefState prev = P->prev;
   uint64_t seq = P->seq, used = 0;
   int D = 0;
-  for (; D < P->run_len && (uint64_t)D < nf; D++) {
+  const int dmax = P->run_len < P->run_max ? P->run_len : P->run_max;
+  if (dmax < 2) return 0;
+  for (; D < dmax && (uint64_t)D < nf; D++) {
     const lcp_frame_in& f = fr[D];
     if (f.n == 0 || f.n > P->N || f.method < 0 || f.method > 2) break;
     bool ok = true;
@@ -1005,10 +1120,12 @@ int plan_run(const lcp_plan_s* P, const lcp_frame_in* fr, uint64_t nf, uint64_t 
     const bool first = P->p.batch_size == 0 ? seq == 0 : seq % (uint64_t)P->p.batch_size == 0;
     const RefState& ref = first ? P->anchor : prev;
     if (!ref.valid || ref.n != f.n) break;
+    if (D > 0 && f.n != fr[0].n) break;  // a run's frames share one size
     used += bound_bytes(P->F, f.n);
     if (used > cap) break;
     rf[D].ref = ref;
     rf[D].q = spare[D & 1];
+    rf[D].chain = D > 0 && !first;
     RefState r = ref;
     r.seq = seq;
     r.q = rf[D].q;
@@ -1019,33 +1136,77 @@ int plan_run(const lcp_plan_s* P, const lcp_frame_in* fr, uint64_t nf, uint64_t 
 }
 
 // Runs D planned frames; ends[k] receives frame k's record end (relative to
-// out) for the committed frames, *committed how many there are.
+// out) for the committed frames, *committed how many there are.  The frames'
+// residuals come from one launch per segment of frames chained on one
+// reference (a segment ends where Alg. 1 turns to the anchor), and all D
+// records from one encode launch set, placed back to back from out.
+constexpr int kRunCopies = 8;    // spread histogram copies per array of a run
+constexpr int kServeCopies = 2;  // ... and per array of a server's merged launch
 lcp_status run_t(lcp_plan_s* P, const lcp_frame_in* fr, int D, const RunFrame* rf, uint8_t* out,
                  uint64_t cap, uint32_t* const* perms, uint64_t* ends, int* committed,
                  hipStream_t s) {
   *committed = 0;
-  launch_fill_u32(reinterpret_cast<uint32_t*>(P->run_dev), 8ull * D, 0u, s);
-  for (int k = 0; k < D; k++) {
-    unsigned long long* slot = P->run_dev + 4 * k;
-    lcp_status st = launch_t(P, fr[k].fields, fr[k].n, rf[k].ref, P->seq + k, out, cap,
-                             P->qpool[rf[k].q], reinterpret_cast<uint32_t*>(slot), slot + 1,
-                             k ? P->run_dev + 4 * (k - 1) + 2 : nullptr, s);
-    if (st) return st;
+  const int F = P->F;
+  const uint64_t n = fr[0].n;
+  uint32_t* words = reinterpret_cast<uint32_t*>(P->run_dev);
+  unsigned long long* offs = P->run_dev + 4 * kTRun;
+  uint32_t* run_err = reinterpret_cast<uint32_t*>(offs + kTRun + 1);
+  const size_t run_words = 4 * kTRun + kTRun + 2;
+  launch_fill_u32(words, 2 * run_words, 0u, s);
+  // residual alphabets are short: unless one recently was not, the packing
+  // kernel builds each array's code (the residual kernel zeroes the word totals)
+  const bool fused = P->fuse_skip == 0 && P->chunk_log2 >= 6 && P->chunk_log2 <= 10;
+  if (P->fuse_skip > 0) P->fuse_skip = P->fuse_skip > D ? P->fuse_skip - D : 0;
+  for (int k0 = 0; k0 < D;) {
+    int k1 = k0 + 1;
+    while (k1 < D && rf[k1].chain) k1++;
+    RunFrames rx;
+    memset(&rx, 0, sizeof(rx));
+    for (int j = k0; j < k1; j++)
+      for (int f = 0; f < F; f++) rx.x[j - k0][f] = fr[j].fields[f];
+    const RefState& ref = rf[k0].ref;
+    launch_t_resid_run(rx, k1 - k0, F, n, t_grid(ref, F), P->ppool[ref.perm], P->qpool[ref.q],
+                       P->qpool[rf[k1 - 1].q], P->run_v8, P->run_esc, P->run_stride, k0,
+                       P->hist_part, P->hist_max, kRunCopies, fused ? P->work : nullptr,
+                       words + 8 * k0, 8, s);
+    k0 = k1;
   }
-  HIP_OK(hipMemcpyAsync(P->run_host, P->run_dev, 32ull * D, hipMemcpyDeviceToHost, s));
+  EncBuild B;
+  B.R = D;
+  B.fused = fused;
+  lcp_status st;
+  for (int k = 0; k < D; k++) {
+    EncRec& rc = P->erec_host[k];
+    memset(&rc, 0, sizeof(rc));
+    rc.h = make_hdr(1, F, 0, P->chunk_log2, F, n, P->seq + k, rf[k].ref.seq, rf[k].ref.grid);
+    rc.a0 = (uint32_t)B.NA;
+    for (int f = 0; f < F; f++) {
+      const uint64_t a = (uint64_t)k * F + f;
+      if ((st = enc_add(P, B, ArrIn{P->run_v8 + a * P->run_stride, 0, nullptr, n,
+                                    P->run_esc + a * P->run_stride},
+                        n, k, (int)(a * kRunCopies), kRunCopies)))
+        return st;
+    }
+  }
+  if ((st = enc_launch(P, B, out, cap, true, s, run_err, offs, nullptr, words, 8))) return st;
+  HIP_OK(hipMemcpyAsync(P->run_host, P->run_dev, 8 * run_words, hipMemcpyDeviceToHost, s));
   HIP_OK(hipStreamSynchronize(s));
-  // a frame flagged for the separate build ends the commits there; the
+  if (g_timer_plan == P) timer_collect(P);
+  const uint32_t launch_err = (uint32_t)(P->run_host[4 * kTRun + kTRun + 1] & 0xFFFFFFFFull);
+  // the encoder's own consistency checks (a chunk beyond its staging slot)
+  if (launch_err & kErrCorrupt) return LCP_ERR_DEVICE;
+  // a frame flagged for the separate code build ends the commits there; the
   // per-frame path codes it again
   for (int k = 0; k < D; k++)
     if ((uint32_t)(P->run_host[4 * k] & 0xFFFFFFFFull) & kErrRebuild) {
       fused_fallback(P, s);
       break;
     }
+  const unsigned long long* ho = P->run_host + 4 * kTRun;
   int c = 0;
-  for (; c < D; c++) {
+  for (; c < D && !(launch_err & kErrCapacity); c++) {
     const uint32_t flags = (uint32_t)(P->run_host[4 * c] & 0xFFFFFFFFull);
-    const uint64_t start = P->run_host[4 * c + 1], end = P->run_host[4 * c + 2];
-    const uint64_t size = end - start;
+    const uint64_t size = ho[c + 1] - ho[c];
     if (flags) break;
     if (fr[c].method == LCP_METHOD_AUTO && (!P->have_last_s || size > P->last_s)) break;
     // committed: LCP-FSM stays in T; Alg. 1 bookkeeping as for any T frame
@@ -1055,14 +1216,14 @@ lcp_status run_t(lcp_plan_s* P, const lcp_frame_in* fr, int D, const RunFrame* r
     P->prev = r;
     if (perms && perms[c]) launch_copy_perm(P->ppool[r.perm], perms[c], fr[c].n, s);
     P->seq++;
-    ends[c] = end;
+    ends[c] = ho[c + 1];
   }
   *committed = c;
   P->run_len = c < D ? kTRunStart : (D == P->run_len && D < kTRun ? 2 * D : P->run_len);
-  // the last committed frame's codes were overwritten if the frame two after
-  // it was launched
-  if (c >= 1 && c + 1 < D) {
-    const int F = P->F;
+  // only the last frame of each segment left its codes, and a later segment
+  // may have reused that slot: after a break, the last committed frame's codes
+  // are rebuilt from its input
+  if (c >= 1 && c < D) {
     launch_t_codes(field_ptrs(fr[c - 1].fields, F), F, fr[c - 1].n, t_grid(P->prev, F),
                    P->ppool[P->prev.perm], P->qpool[P->prev.q], P->err, s);
     P->err_clean = false;
@@ -1545,12 +1706,16 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   const int F = P->F, RB = P->RB;
   const uint64_t ntiles = (NB + kSortTile - 1) / kSortTile + RB;  // tiles never cross frames
   P->NAmax = RB * (F + 2);
+  if (P->run_max * F > P->NAmax) P->NAmax = P->run_max * F;  // a run's arrays
   const uint64_t NA = (uint64_t)P->NAmax;
+  const uint64_t RR = (uint64_t)(RB > P->run_max ? RB : P->run_max);  // records per launch set
   // spread histogram copies: enc_hist_copies(n) <= 1 + (1 + n / 8192) / 16 per
   // array; the residual kernel uses kHistCopies per field
   uint64_t hc = 2 * NA + (uint64_t)(F + 2) * NB / 131072 + 1;
   if (hc > NA * kHistCopies) hc = NA * kHistCopies;
   if (hc < (uint64_t)kMaxF * kHistCopies) hc = (uint64_t)kMaxF * kHistCopies;
+  if (hc < (uint64_t)P->run_max * F * kRunCopies) hc = (uint64_t)P->run_max * F * kRunCopies;
+  if (P->serve_batch && hc < (uint64_t)RB * F * kServeCopies) hc = (uint64_t)RB * F * kServeCopies;
   P->hist_copies = hc;
   P->cw_cap = (uint64_t)(F + 2) * NB / (1ull << P->chunk_log2) + NA + 1;
   // staging: enc_stage_words summed over a batch's arrays; per array type a
@@ -1559,24 +1724,32 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   P->stage_cap = ((uint64_t)2 * enc_slot_words(true, P->chunk_log2) +
                   (uint64_t)F * enc_slot_words(false, P->chunk_log2)) *
                  ((NB >> P->chunk_log2) + RB + 1);
+  // a run's arrays: run_max * F byte arrays of at most N values
+  const uint64_t run_chunks = (uint64_t)P->run_max * F * ((N >> P->chunk_log2) + 1);
+  if (P->cw_cap < run_chunks + NA + 1) P->cw_cap = run_chunks + NA + 1;
+  if (P->stage_cap < run_chunks * enc_slot_words(false, P->chunk_log2))
+    P->stage_cap = run_chunks * enc_slot_words(false, P->chunk_log2);
+  P->run_stride = (N + 63) & ~(uint64_t)63;
   uint64_t sn = NB > 256 * ntiles ? NB : 256 * ntiles;
   P->scan_tmp_n = scan_tmp_elems(sn);
   P->rec_tmp_cap = bound_bytes(F, N);
-  D.add(&P->keys0, NB);
-  D.add(&P->keys1, NB);
-  D.add(&P->ids, NB);
-  D.add(&P->v_id, NB);
-  D.add(&P->v_cnt, NB);
-  D.add(&P->prel, NB);
-  D.add(&P->vals0, NB);
-  D.add(&P->vals1, NB);
-  D.add(&P->hist, 256 * ntiles);
-  D.add(&P->flags, NB);
-  D.add(&P->starts, NB);
+  const bool sb = P->serve_batch;
+  const uint64_t NS = sb ? 0 : NB;  // the spatial path's per-particle buffers
+  D.add(&P->keys0, NS);
+  D.add(&P->keys1, NS);
+  D.add(&P->ids, NS);
+  D.add(&P->v_id, NS);
+  D.add(&P->v_cnt, NS);
+  D.add(&P->slot_rec, NS * (uint64_t)slot_rec_words(F));
+  D.add(&P->vals0, NS);
+  D.add(&P->vals1, NS);
+  D.add(&P->hist, sb ? 0 : 256 * ntiles);
+  D.add(&P->flags, NS);
+  D.add(&P->starts, NS);
   D.add(&P->v_slot, (uint64_t)F * NB);
-  if (P->p.multi_frame) {
+  if (P->p.multi_frame || sb) {
     D.add(&P->v_byte, (uint64_t)F * NB);
-    D.add(&P->dres8, (uint64_t)kDecSlots * F * NB);
+    D.add(&P->dres8, (uint64_t)(sb ? 1 : kDecSlots) * F * NB);
   } else {
     P->v_byte = nullptr;
     P->dres8 = nullptr;
@@ -1586,7 +1759,7 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   // decode-only tables: 2^13 LUT entries per array of a decode launch, header
   // staging, descriptor tables, block corners
   const uint64_t dec_arrays = P->compress_only ? 0 : kMaxBatchArrays + 2 * kMaxBatchFrames;
-  const uint64_t dec_frames = P->compress_only ? 0 : kMaxBatchFrames;
+  const uint64_t dec_frames = P->compress_only ? 0 : (sb && RB > kMaxBatchFrames ? (uint64_t)RB : kMaxBatchFrames);
   D.add(&P->lut, dec_arrays << kMaxLen);
   D.add(&P->ext_part, (uint64_t)2 * kMaxF * kSegExtCap * RB);
   D.add(&P->hist_part, hc * kAlphabet);
@@ -1597,27 +1770,35 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   D.add(&P->blobtab_dev, 2 * dec_frames);
   D.add(&P->arrtab_dev, dec_arrays);
   D.add(&P->prefix_dev, 2 * dec_arrays);
-  D.add(&P->corner, P->compress_only ? 0 : 3 * NB);
+  D.add(&P->corner, P->compress_only || sb ? 0 : 3 * NB);
   D.add(&P->scan_tmp, P->scan_tmp_n);
   D.add(&P->work, NA);
   D.add(&P->ret_dev, 2 + (uint64_t)RB + (uint64_t)RB * F);
-  D.add(&P->run_dev, 4 * kTRun);
+  D.add(&P->run_dev, 4 * kTRun + kTRun + 2);
+  D.add(&P->run_v8, (uint64_t)P->run_max * F * P->run_stride);
+  D.add(&P->run_esc, (uint64_t)P->run_max * F * P->run_stride);
   // tables uploaded together are adjacent, with the same sizes as their host
   // staging (seg + segpre, dseg + dpre, erec + earr + epre)
   D.add(&P->seg_dev, RB);
   D.add(&P->segpre_dev, 4 * ((uint64_t)RB + 1));
   D.add(&P->dseg_dev, dec_frames);
   D.add(&P->dpre_dev, P->compress_only ? 0 : 2 * (kMaxBatchFrames + 1));
-  D.add(&P->erec_dev, RB);
+  D.add(&P->erec_dev, RR);
   D.add(&P->earr_dev, NA);
   D.add(&P->epre_dev, 4 * (NA + 1));
   D.add(&P->rstart, (uint64_t)RB + 1);
   D.add(&P->Bs, RB);
   D.add(&P->permdst_dev, RB);
   D.add(&P->segbase, 3 * dec_frames);
+  if (sb) P->rec_tmp_cap = bound_bytes(F, NB) + 4096ull * RB;  // records of a merged launch
   D.add(&P->rec_tmp, P->compress_only ? 0 : P->rec_tmp_cap);
+  D.add(&P->tfr_dev, sb ? RB : 0);
+  D.add(&P->trc_dev, sb ? RB : 0);
+  D.add(&P->spre_dev, sb ? (uint64_t)RB + 1 : 0);
+  D.add(&P->sret_dev, sb ? 2 * (uint64_t)RB + 2 : 0);
+  D.add(&P->sdst_dev, sb ? 2 * (uint64_t)RB : 0);
   H.add(&P->ret_host, 2 + (size_t)RB + (size_t)RB * F);
-  H.add(&P->run_host, 4 * kTRun);
+  H.add(&P->run_host, 4 * kTRun + kTRun + 2);
   H.add(&P->hdr_host, (size_t)kHdrStage * dec_frames);
   H.add(&P->blobtab_host, 2 * dec_frames);
   H.add(&P->arrtab_host, dec_arrays);
@@ -1626,10 +1807,15 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   H.add(&P->segpre_host, 4 * ((size_t)RB + 1));
   H.add(&P->dseg_host, dec_frames);
   H.add(&P->dpre_host, P->compress_only ? 0 : 2 * (kMaxBatchFrames + 1));
-  H.add(&P->erec_host, RB);
+  H.add(&P->erec_host, RR);
   H.add(&P->earr_host, NA);
   H.add(&P->epre_host, 4 * (NA + 1));
   H.add(&P->permdst_host, RB);
+  H.add(&P->tfr_host, sb ? RB : 0);
+  H.add(&P->trc_host, sb ? RB : 0);
+  H.add(&P->spre_host, sb ? (size_t)RB + 1 : 0);
+  H.add(&P->sret_host, sb ? 2 * (size_t)RB + 2 : 0);
+  H.add(&P->sdst_host, sb ? 2 * (size_t)RB : 0);
 }
 
 // Resident stream state of multi-frame plans: the compressor's candidate and
@@ -1652,6 +1838,7 @@ void bind_scratch(lcp_plan_s* P, void* dev, void* host, hipStream_t s) {
   D.place(dev);
   H.place(host);
   P->enc_cache_ok = false;
+  drop_graphs(P);  // they hold the scratch pointers of the last binding
   P->err = reinterpret_cast<uint32_t*>(P->ret_dev);
   P->offs_dev = P->ret_dev + 1;
   P->ext_dev = reinterpret_cast<uint32_t*>(P->ret_dev + 2 + P->RB);
@@ -1674,13 +1861,37 @@ lcp_status alloc_state(lcp_plan_s* P) {
   return LCP_OK;
 }
 
+// Frames a temporal run of a multi-frame plan codes at once: as many as keep
+// the run's buffers (residual bytes, escapes, staging, histogram copies) within
+// kRunBytes, at most kRunMax; fewer than two means no runs.
+constexpr uint64_t kRunBytes = 1ull << 30;
+int run_frames_for(const lcp_plan_s* P) {
+  if (!P->p.multi_frame) return 0;
+  const uint64_t N = P->N, F = (uint64_t)P->F;
+  const uint64_t chunks = (N >> P->chunk_log2) + 1;
+  const uint64_t per = F * ((N + 63) & ~63ull) * 5 + F * chunks * 4 * (enc_slot_words(false, P->chunk_log2) + 1) +
+                       F * kRunCopies * kAlphabet * 4ull;
+  uint64_t d = kRunBytes / per;
+  if (d > (uint64_t)kRunMax) d = kRunMax;
+  return d < 2 ? 0 : (int)d;
+}
+
 lcp_status alloc_plan(lcp_plan_s* P) {
   Layout D, H, S;
+  P->run_max = run_frames_for(P);
   layout_scratch(P, D, H);
   layout_state(P, S);
+  const size_t state = S.items.empty() ? 0 : S.total;
+  // within a budget, temporal runs get fewer frames, then none, before the plan fails
+  while (P->p.hbm_budget_bytes && D.total + state > P->p.hbm_budget_bytes && P->run_max > 0) {
+    P->run_max = P->run_max > 2 ? P->run_max / 2 : 0;
+    D = Layout();
+    H = Layout();
+    layout_scratch(P, D, H);
+  }
   P->scratch_bytes = D.total;
   P->host_bytes = H.total;
-  const size_t need = D.total + (S.items.empty() ? 0 : S.total);
+  const size_t need = D.total + state;
   if (P->p.hbm_budget_bytes && need > P->p.hbm_budget_bytes) return LCP_ERR_BUDGET;
   HIP_OK(hipMalloc(&P->own_dev, D.total));
   HIP_OK(hipHostMalloc(&P->own_host, H.total, 0));
@@ -1692,6 +1903,8 @@ lcp_status alloc_plan(lcp_plan_s* P) {
 }
 
 void free_plan(lcp_plan_s* P) {
+  drop_graphs(P);
+  if (P->cap_stream) (void)hipStreamDestroy(P->cap_stream);
   if (P->own_dev) (void)hipFree(P->own_dev);
   if (P->state_dev) (void)hipFree(P->state_dev);
   if (P->own_host) (void)hipHostFree(P->own_host);
@@ -1778,6 +1991,25 @@ lcp_status compress_group(lcp_plan_s* P, int R, const lcp_frame_in* fr, uint8_t*
   return LCP_OK;
 }
 
+// The autotuner's choices, shared by every plan of the process: (GPU name and
+// compute units, bit width of a call's total particles, fields) -> shape.
+std::mutex g_tune_mu;
+std::map<std::tuple<std::string, int, int>, lcp_tuning> g_tune_cache;
+const lcp_tuning kDefaultTuning{1024, 0, 0, 1};
+
+std::tuple<std::string, int, int> tune_key(const lcp_plan_s* P, uint64_t particles) {
+  return std::make_tuple(P->dev_key, bitwidth64(particles), P->F);
+}
+
+// The launch shape for a call of `particles` particles: the plan's own
+// setting, else the cached choice for its key, else the defaults.
+void pick_tuning(lcp_plan_s* P, uint64_t particles) {
+  if (P->tune_set) return;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  auto it = g_tune_cache.find(tune_key(P, particles));
+  P->tune = it != g_tune_cache.end() ? it->second : kDefaultTuning;
+}
+
 // Single-frame plans: independent frames in batches of up to RB frames and
 // NB particles, each batch one extent pass and one LCP-S launch set.
 lcp_status compress_independent(lcp_plan_s* plan, uint64_t n_frames, const lcp_frame_in* frames,
@@ -1786,6 +2018,9 @@ lcp_status compress_independent(lcp_plan_s* plan, uint64_t n_frames, const lcp_f
   uint64_t off = 0;
   out_offsets[0] = 0;
   std::vector<uint64_t> offs((size_t)plan->RB + 1);
+  uint64_t particles = 0;
+  for (uint64_t j = 0; j < n_frames; j++) particles += frames[j].n;
+  pick_tuning(plan, particles);
   for (uint64_t j = 0; j < n_frames;) {
     int R = 0;
     uint64_t tot = 0;
@@ -1864,6 +2099,9 @@ lcp_status plan_setup(const lcp_params* params, const float* const* sample_field
   if (hipSetDevice(params->device) != hipSuccess) return LCP_ERR_DEVICE;
   lcp_plan_s* P = new lcp_plan_s();
   plan_fill(P, *params);
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, params->device) == hipSuccess)
+    P->dev_key = std::string(prop.gcnArchName) + "/" + std::to_string(prop.multiProcessorCount);
   *out = P;
   return LCP_OK;
 }
@@ -1872,7 +2110,7 @@ lcp_status plan_setup(const lcp_params* params, const float* const* sample_field
 namespace lcp {
 bool ktimer_events(const char* name, uint64_t bytes, hipEvent_t* start, hipEvent_t* stop) {
   lcp_plan_s* P = g_timer_plan;
-  if (!P || !P->timer_name[0] || strcmp(P->timer_name, name) != 0) return false;
+  if (!P || P->capturing || !P->timer_name[0] || strcmp(P->timer_name, name) != 0) return false;
   if (P->timer_seen++ % kTimerStride != 0) return false;
   *start = timer_event(P);
   *stop = timer_event(P);
@@ -2077,6 +2315,90 @@ lcp_status lcp_select(lcp_plan_t plan, int* decision) {
   return LCP_OK;
 }
 
+lcp_status lcp_plan_set_tuning(lcp_plan_t plan, const lcp_tuning* t) {
+  if (!plan || !t || t->tile < 256 || t->tile > 16384 || t->tile % 256 || t->grid > (1u << 20) ||
+      t->slot_grid > (1u << 20) || (t->graphs != 0 && t->graphs != 1))
+    return LCP_ERR_ARG;
+  plan->tune = *t;
+  plan->tune_set = true;
+  return LCP_OK;
+}
+
+lcp_status lcp_plan_get_tuning(lcp_plan_t plan, lcp_tuning* t) {
+  if (!plan || !t) return LCP_ERR_ARG;
+  *t = plan->tune;
+  return LCP_OK;
+}
+
+lcp_status lcp_plan_autotune(lcp_plan_t plan, uint64_t n_frames, const lcp_frame_in* frames,
+                             void* out, uint64_t out_cap, int reps, hipStream_t stream,
+                             lcp_tuning* chosen, double* best_ms, double* default_ms) {
+  if (!plan || plan->p.multi_frame || !frames || n_frames == 0 || !out || ((uintptr_t)out & 3) ||
+      !plan->bound || reps < 1)
+    return LCP_ERR_ARG;
+  int cus = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, plan->p.device) != hipSuccess ||
+      cus < 1)
+    return LCP_ERR_DEVICE;
+  std::vector<lcp_tuning> cand;
+  for (uint32_t tile : {1024u, 2048u, 4096u})
+    for (uint32_t g : {0u, 8u, 32u})
+      for (uint32_t sg : {0u, 16u}) cand.push_back(lcp_tuning{tile, g * cus, sg * cus, 1});
+  std::vector<uint64_t> offs(n_frames + 1);
+  const uint64_t seq0 = plan->seq;
+  const lcp_tuning saved = plan->tune;
+  const bool saved_set = plan->tune_set;
+  TimerScope ts(plan);
+  // best-of-reps wall time of one call (each call waits for its records), the
+  // first call of a shape capturing its graph untimed
+  auto time_of = [&](const lcp_tuning& t, double* ms) -> lcp_status {
+    plan->tune = t;
+    plan->tune_set = true;
+    double best = 1e30;
+    for (int r = -1; r < reps; r++) {
+      plan->seq = seq0;
+      const auto t0 = std::chrono::steady_clock::now();
+      lcp_status st = compress_independent(plan, n_frames, frames, reinterpret_cast<uint8_t*>(out),
+                                           out_cap, offs.data(), nullptr, nullptr, stream);
+      const auto t1 = std::chrono::steady_clock::now();
+      if (st) return st;
+      if (r >= 0) best = std::min(best, std::chrono::duration<double, std::milli>(t1 - t0).count());
+    }
+    *ms = best;
+    return LCP_OK;
+  };
+  double dflt = 0, best = 1e30;
+  lcp_tuning pick = kDefaultTuning;
+  lcp_status st = time_of(kDefaultTuning, &dflt);
+  best = dflt;
+  for (size_t i = 0; !st && i < cand.size(); i++) {
+    double ms = 0;
+    st = time_of(cand[i], &ms);
+    if (!st && ms < best) {
+      best = ms;
+      pick = cand[i];
+    }
+  }
+  plan->seq = seq0;
+  if (st) {
+    plan->tune = saved;
+    plan->tune_set = saved_set;
+    return st;
+  }
+  plan->tune = pick;
+  plan->tune_set = true;
+  uint64_t particles = 0;
+  for (uint64_t j = 0; j < n_frames; j++) particles += frames[j].n;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune_cache[tune_key(plan, particles)] = pick;
+  }
+  if (chosen) *chosen = pick;
+  if (best_ms) *best_ms = best;
+  if (default_ms) *default_ms = dflt;
+  return LCP_OK;
+}
+
 lcp_status lcp_kernel_timer_set(lcp_plan_t plan, const char* kernel_name) {
   if (!plan) return LCP_ERR_ARG;
   if (!kernel_name) {
@@ -2103,6 +2425,7 @@ lcp_status lcp_kernel_timer_read(lcp_plan_t plan, double* total_ms, uint64_t* la
 }
 
 }  // extern "C"
+
 
 // ================================================================== no-allocation entry point
 // lcp_compress_static runs the single-frame LCP-S path of lcp_compress on

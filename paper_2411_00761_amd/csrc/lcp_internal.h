@@ -114,7 +114,8 @@ struct DSegDev {
 };
 constexpr int kMaxBatch = 1024;       // frames per spatial batch
 constexpr uint32_t kSegExtCap = 256;  // extent workgroups per frame (at most)
-constexpr uint32_t kSeg1k = 1024;     // slots per workgroup, element-wise kernels
+constexpr uint32_t kSeg1k = 1024;     // slots per workgroup, element-wise kernels (decode side;
+                                      // the encode side's tile is tuned, see TileShape)
 constexpr uint32_t kSeg256 = 256;     // slots per workgroup, slot symbol kernel
 uint32_t seg_ext_blocks(uint64_t n);
 
@@ -179,32 +180,47 @@ void plan_unbind(lcp_plan_s* P);
 // ceil(n / kSeg256) and ceil(n / kSortTile).  ext receives R x 2F sortable keys (min, max per field).
 void launch_extent_b(const SegDev* S, const uint32_t* pre_ext, uint32_t ext_blocks, int R, int F,
                      uint32_t* ext, uint32_t* part, uint32_t* err, uint64_t bytes, hipStream_t s);
-// prel receives each particle's three in-block offsets (16 bits apart), input order.
-void launch_quant_key_b(const SegDev* S, const uint32_t* pre_1k, uint32_t blocks, int R,
-                        uint64_t* keys, uint32_t* vals, uint64_t* prel, uint64_t ntot,
+// rec receives, per particle in input order, a record of slot_rec_words(F)
+// words: its three in-block offsets (16 bits apart) and its supplementary
+// fields' codes.
+int slot_rec_words(int F);
+// The element-wise encode kernels of a batch walk `tiles` tiles of `tile`
+// slots (a multiple of 256; the prefix tables count tiles per frame) with a
+// persistent grid of `grid` workgroups (0: one workgroup per tile).  Launch
+// shape only: the results do not depend on it.
+struct TileShape {
+  uint32_t tile, tiles, grid;
+};
+void launch_quant_key_b(const SegDev* S, const uint32_t* pre_tile, const TileShape& ts, int R,
+                        int F, uint64_t* keys, uint32_t* vals, uint32_t* rec, uint64_t ntot,
                         hipStream_t s);
 // Non-empty blocks of every frame: ids, global start slots,
 // rstart[r] (first block of frame r; rstart[R] = all blocks) and Bs[r].
-void launch_runs_b(const uint64_t* keys, const SegDev* S, const uint32_t* pre_1k, uint32_t blocks,
-                   int R, uint64_t ntot, uint32_t* flags_scan, uint64_t* ids, uint32_t* starts,
-                   uint32_t* rstart, uint32_t* Bs, uint32_t* tmp32, hipStream_t s);
+void launch_runs_b(const uint64_t* keys, const SegDev* S, const uint32_t* pre_tile,
+                   const TileShape& ts, int R, uint64_t ntot, uint32_t* flags_scan, uint64_t* ids,
+                   uint32_t* starts, uint32_t* rstart, uint32_t* Bs, uint32_t* tmp32,
+                   hipStream_t s);
 // Block symbols of frame r go to v_id / v_cnt + S[r].off.
 void launch_block_syms_b(const uint64_t* ids, const uint32_t* starts, const uint32_t* rstart,
                          int R, const SegDev* S, uint64_t ntot, uint64_t* v_id, uint64_t* v_cnt,
                          hipStream_t s);
-// v_rel: [3][ntot], v_sup: [F-3][ntot]; q_slot (nullable): [F][ntot].
-void launch_slot_syms_b(const SegDev* S, const uint32_t* pre_256, uint32_t blocks, int R, int F,
-                        const uint32_t* perm, const uint64_t* prel, uint64_t ntot, uint32_t* v_rel,
-                        uint32_t* v_sup, int32_t* q_slot, hipStream_t s);
+// v_rel: [3][ntot], v_sup: [F-3][ntot]; q_slot (nullable): [F][ntot]; keys:
+// the sorted block keys (slot order).
+void launch_slot_syms_b(const SegDev* S, const uint32_t* pre_256, uint32_t tiles, uint32_t grid,
+                        int R, int F, const uint32_t* perm, const uint64_t* keys,
+                        const uint32_t* rec, uint64_t ntot, uint32_t* v_rel, uint32_t* v_sup,
+                        int32_t* q_slot, hipStream_t s);
 // dst[r] (device table of device pointers, entries may be null) <- perm slice of frame r.
-void launch_copy_perm_b(const uint32_t* perm, const SegDev* S, const uint32_t* pre_1k,
-                        uint32_t blocks, int R, uint32_t* const* dst, hipStream_t s);
+void launch_copy_perm_b(const uint32_t* perm, const SegDev* S, const uint32_t* pre_tile,
+                        const TileShape& ts, int R, uint32_t* const* dst, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) by the low `bits` key bits, within
 // each frame of the SegDev table (pre_tile: ceil(n / kSortTile) tiles per
 // frame, ntiles in all; hist: 256 * ntiles u32).  Returns the buffer index
 // (0: k0/v0, 1: k1/v1) that holds the result.
 constexpr uint32_t kSortTile = 4096;
+// The buffer (0: k0/v0, 1: k1/v1) a sort of `bits` key bits leaves its result in.
+int radix_result(int bits);
 int radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, const SegDev* S,
                const uint32_t* pre_tile, uint32_t ntiles, int R, uint64_t ntot, int bits,
                uint32_t* hist, uint32_t* tmp32, hipStream_t s);
@@ -241,6 +257,51 @@ void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
                     const uint32_t* perm_ref, const int32_t* q_ref, uint8_t* v8, uint32_t* v_res,
                     int32_t* q_new, uint32_t* err, uint32_t* hist_part,
                     unsigned long long* hist_max, ArrWork* zero_words, hipStream_t s);
+// A temporal run: up to kRunMax frames coded as a chain on one reference grid
+// and slot order in one launch (frame j's fields fr.x[j]); see k_t_resid_run.
+constexpr int kRunMax = 8;
+struct RunFrames {
+  const float* x[kRunMax][kMaxF];
+};
+void launch_t_resid_run(const RunFrames& fr, int J, int F, uint64_t n, const GridDev& g,
+                        const uint32_t* perm, const int32_t* q_ref, int32_t* q_last, uint8_t* v8,
+                        uint32_t* vesc, uint64_t astride, int a0, uint32_t* hist_part,
+                        unsigned long long* hist_max, int copies, ArrWork* zero_words,
+                        uint32_t* err, int err_stride, hipStream_t s);
+// Temporal frames of different streams in one launch (the served form): each
+// frame has its own size, reference grid, slot order and reference codes, and
+// its own residual buffers; workgroups find their frame through a prefix table
+// of per-frame workgroup counts.  Frame r's arrays are r * F + f of the launch
+// (histogram copies [(r F + f) copies, +copies), work records zw[r F + f]).
+struct TFrameDev {
+  const float* x[kMaxF];
+  const uint32_t* perm;   // reference slot -> input index
+  const int32_t* q_ref;   // reference codes [F][n]
+  int32_t* q_new;         // the frame's codes [F][n]
+  uint8_t* v8;            // residual bytes, field f at v8 + f * n
+  uint32_t* esc;          // escaped residuals, field f at esc + f * n
+  uint32_t* err;          // the frame's error word
+  uint64_t n;
+  int vec, pad;
+  GridDev g;
+};
+uint32_t t_multi_blocks(uint64_t n, int vec);
+void launch_t_resid_multi(const TFrameDev* frames, const uint32_t* pre, uint32_t blocks, int R,
+                          int F, uint32_t* hist_part, unsigned long long* hist_max, int copies,
+                          ArrWork* zero_words, uint64_t bytes, hipStream_t s);
+// Temporal frames of different streams reconstructed in one launch: frame r's
+// residual bytes (-128: the int32 residual is in out[f] at the same index) are
+// added to its reference codes; the values go to out, the codes to q_new.
+struct TReconDev {
+  const int32_t* q_ref;
+  int32_t* q_new;
+  const int8_t* r8;  // field f at r8 + f * n
+  float* out[kMaxF];
+  uint64_t n;
+  float m[kMaxF], eb_q[kMaxF];
+};
+void launch_t_recon_multi(const TReconDev* frames, const uint32_t* pre, uint32_t blocks, int R,
+                          int F, uint32_t* err, uint64_t bytes, hipStream_t s);
 void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, uint64_t B,
                      uint64_t n, uint64_t total_blocks, const uint32_t* bn, int k,
                      uint32_t* corner, uint32_t* mark, uint32_t* err, hipStream_t s);
@@ -305,6 +366,11 @@ struct EncLaunch {
   // temporal record whose packing builds the code itself (all_bytes, a chunk
   // per wave): no build launch; the emit clears the histogram copies
   int fused;
+  // non-null: a record whose packing could not build its code flags
+  // kErrRebuild at err_rec + record * err_stride instead of in the launch's
+  // error word (a run of temporal records learns which frame it was)
+  uint32_t* err_rec;
+  int err_stride;
 };
 // Coding scratch of a launch set: a word count per chunk and the staging of
 // the Huffman payloads before they move into their records.

@@ -26,7 +26,8 @@ EXPORTED = ["lcp_plan", "lcp_plan_destroy", "lcp_plan_reset", "lcp_plan_block_lo
             "lcp_decompress", "lcp_select", "lcp_status_string", "lcp_kernel_timer_set",
             "lcp_kernel_timer_read", "lcp_server_create", "lcp_server_destroy",
             "lcp_server_open_stream", "lcp_server_submit", "lcp_server_wait",
-            "lcp_scratch_bytes", "lcp_compress_static"]
+            "lcp_scratch_bytes", "lcp_compress_static", "lcp_plan_set_tuning",
+            "lcp_plan_get_tuning", "lcp_plan_autotune"]
 REQ_COMPRESS, REQ_DECOMPRESS = 1, 2
 
 
@@ -43,6 +44,11 @@ class lcp_params(C.Structure):
                 ("chunk_log2", C.c_int), ("max_particles", C.c_uint64),
                 ("hbm_budget_bytes", C.c_uint64), ("device", C.c_int),
                 ("max_batch_particles", C.c_uint64), ("max_batch_frames", C.c_int)]
+
+
+class lcp_tuning(C.Structure):
+    _fields_ = [("tile", C.c_uint32), ("grid", C.c_uint32), ("slot_grid", C.c_uint32),
+                ("graphs", C.c_int)]
 
 
 class lcp_frame_in(C.Structure):
@@ -150,6 +156,11 @@ def lib():
         L.lcp_scratch_bytes.argtypes = [C.POINTER(lcp_params), C.POINTER(C.c_uint64)]
         L.lcp_compress_static.argtypes = [C.POINTER(lcp_params), C.c_uint64, P, P, C.c_uint64, P,
                                           P, P]
+        L.lcp_plan_set_tuning.argtypes = [P, C.POINTER(lcp_tuning)]
+        L.lcp_plan_get_tuning.argtypes = [P, C.POINTER(lcp_tuning)]
+        L.lcp_plan_autotune.argtypes = [P, C.c_uint64, P, P, C.c_uint64, C.c_int, P,
+                                        C.POINTER(lcp_tuning), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]
         L.lcp_server_create.argtypes = [C.POINTER(lcp_server_params), C.POINTER(P)]
         L.lcp_server_destroy.argtypes = [P]
         L.lcp_server_destroy.restype = None
@@ -279,6 +290,28 @@ class Plan:
         """Particle count from a record header (bytes 16..23, little-endian)."""
         b = buf[offset + 16: offset + 24].cpu().numpy().tobytes()
         return int.from_bytes(b, "little")
+
+    def set_tuning(self, tile: int = 1024, grid: int = 0, slot_grid: int = 0, graphs: bool = True):
+        t = lcp_tuning(tile, grid, slot_grid, int(graphs))
+        _check(lib().lcp_plan_set_tuning(self.h, C.byref(t)), "lcp_plan_set_tuning")
+
+    def tuning(self) -> dict:
+        t = lcp_tuning()
+        _check(lib().lcp_plan_get_tuning(self.h, C.byref(t)), "lcp_plan_get_tuning")
+        return {"tile": t.tile, "grid": t.grid, "slot_grid": t.slot_grid, "graphs": bool(t.graphs)}
+
+    def autotune(self, frames: Sequence, out, reps: int = 2):
+        """lcp_plan_autotune on these frames; returns (choice dict, best ms, default ms)."""
+        import torch
+        frames = [f if f.is_contiguous() else f.contiguous() for f in frames]
+        fin, keep = frame_in_table(frames, self.F)
+        t, best, dflt = lcp_tuning(), C.c_double(), C.c_double()
+        _check(lib().lcp_plan_autotune(self.h, len(frames), fin, out.data_ptr(), out.numel(), reps,
+                                       torch.cuda.current_stream(self.device).cuda_stream,
+                                       C.byref(t), C.byref(best), C.byref(dflt)),
+               "lcp_plan_autotune")
+        return ({"tile": t.tile, "grid": t.grid, "slot_grid": t.slot_grid,
+                 "graphs": bool(t.graphs)}, best.value, dflt.value)
 
     def timer_set(self, name):
         _check(lib().lcp_kernel_timer_set(self.h, None if name is None else name.encode()),

@@ -86,8 +86,10 @@ def test_static_entry_refuses_on_the_host():
         return L.lcp_compress_static(C.byref(p), 0, None, None, 0, offs, None, None)
 
     assert call(1 << 20) == lcp.ERR_BUDGET          # 2^20 particles need more than 64 MiB
-    assert call(553409) == lcp.ERR_BUDGET           # one past the three-field limit
-    assert call(436929, F=6) == lcp.ERR_BUDGET      # one past the six-field limit
+    assert call(500000) != lcp.ERR_BUDGET           # about 550,000 three-field particles fit
+    assert call(600000) == lcp.ERR_BUDGET
+    assert call(340000, F=6) != lcp.ERR_BUDGET      # about 370,000 of six fields
+    assert call(400000, F=6) == lcp.ERR_BUDGET
     assert call(1000, frames=64) == lcp.ERR_BUDGET  # 64 frames per launch set
     assert call(1000, multi=1) == lcp.ERR_ARG       # LCP-S only
     assert call(1000, k=-1) == lcp.ERR_ARG          # no block-size search

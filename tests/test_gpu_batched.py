@@ -108,3 +108,58 @@ def test_batch_errors_leave_no_partial_state(lcp):
     rec = out[offs[0]:offs[1]].cpu().numpy().tobytes()
     want, _, _ = O.compress_s(xs[0], O.grids_for(xs[0], O.EB_REL_GLOBAL, 1e-4), 4, 10, 0)
     assert rec == want
+
+
+def test_graph_replays_tunings_and_autotune(lcp):
+    """Batches of one launch shape: the first call captures the kernels into a
+    graph, later calls replay it on other frames of the same sizes (other
+    values, grids and block counts) -- every record and permutation is the
+    oracle's for its frame and sequence number.  Other launch shapes (tile,
+    persistent grids), graphs switched off, and the autotuner's choice give
+    the same bytes."""
+    sizes = [5000, 70001, 3, 20000, 131072, 777]
+    rng = np.random.default_rng(23)
+
+    def frames(seed):
+        r = np.random.default_rng(seed)
+        return [datagen.uniform_frame(n, hi=100.0, seed=seed + j) if j % 2 == 0
+                else datagen.clustered_positions(r, n, 100.0, 15, 0.3) for j, n in enumerate(sizes)]
+
+    A, B = frames(31), frames(57)
+    tot = sum(sizes)
+    plan = lcp.Plan(1e-4, lcp.EB_REL_GLOBAL, block_log2=5, max_particles=max(sizes),
+                    max_batch_particles=tot, max_batch_frames=len(sizes))
+    out = torch.empty(sum(plan.bound(n) + 4 for n in sizes), dtype=torch.uint8, device="cuda")
+    seq = 0
+
+    def check(xs, label):
+        nonlocal seq
+        xd = [torch.from_numpy(x).cuda() for x in xs]
+        _, offs, used, perms = plan.compress(xd, out=out, want_perm=True)
+        buf = out[:offs[-1]].cpu().numpy().tobytes()
+        for j, x in enumerate(xs):
+            want, wperm, _ = O.compress_s(x, O.grids_for(x, O.EB_REL_GLOBAL, 1e-4), 5, 10, seq + j)
+            assert buf[offs[j]:offs[j + 1]] == want, (label, j)
+            assert np.array_equal(perms[j].cpu().numpy().astype(np.uint32), wperm), (label, j)
+        seq += len(xs)
+
+    for rep, xs in enumerate([A, B, A, B]):  # capture, then replays
+        check(xs, f"graph {rep}")
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    for t in [(4096, 0, 0, True), (2048, 8 * cus, 16 * cus, True), (256, 2, 1, True),
+              (1024, 0, 0, False), (16384, 32 * cus, 0, False)]:
+        plan.set_tuning(*t)
+        assert plan.tuning() == {"tile": t[0], "grid": t[1], "slot_grid": t[2], "graphs": t[3]}
+        check(B, f"tuning {t}")
+    with pytest.raises(lcp.LCPError):
+        plan.set_tuning(1000, 0, 0, True)  # not a multiple of 256
+    tuned = lcp.Plan(1e-4, lcp.EB_REL_GLOBAL, block_log2=5, max_particles=max(sizes),
+                     max_batch_particles=tot, max_batch_frames=len(sizes))
+    xd = [torch.from_numpy(x).cuda() for x in A]
+    choice, best, dflt = tuned.autotune(xd, out, reps=1)
+    assert best <= dflt and choice["tile"] in (1024, 2048, 4096)
+    _, offs, _, _ = tuned.compress(xd, out=out)
+    buf = out[:offs[-1]].cpu().numpy().tobytes()
+    for j, x in enumerate(A):  # the autotuner left the sequence numbers as they were
+        want, _, _ = O.compress_s(x, O.grids_for(x, O.EB_REL_GLOBAL, 1e-4), 5, 10, j)
+        assert buf[offs[j]:offs[j + 1]] == want, j

@@ -130,3 +130,32 @@ def test_tight_buffer_stops_at_the_frame_that_does_not_fit(lcp):
     assert f"needs {sum(sizes[:11])} bytes" in str(ei.value)
     buf = out.cpu().numpy().tobytes()
     assert buf[:sum(sizes[:10])] == b"".join(r for r, _, _ in want[:10])
+
+
+@pytest.mark.parametrize("n,batch", [(20003, 4), (4096 * 3 + 1, 0)])
+def test_runs_ragged_size_and_segments(lcp, n, batch):
+    """Runs on the residual kernel's one-slot-per-thread path (n not a multiple
+    of four), split into segments where Alg. 1 turns to the anchor (batches of
+    four) or one unbounded chain: records, methods and permutations against
+    the oracle stream, and the stream decoded in one call."""
+    tr = datagen.MDTrajectory(n, seed=17, step=0.002)
+    xs = [tr.next_frame() for _ in range(30)]
+    ost = O.Stream(O.EB_REL_GLOBAL, EB, batch_size=batch, block_log2=4, max_n=n)
+    plan = lcp.Plan(EB, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=batch, block_log2=4,
+                    max_particles=n)
+    out, offs, used, perms = plan.compress([torch.from_numpy(x).cuda() for x in xs], want_perm=True)
+    recs = []
+    for t, x in enumerate(xs):
+        want, wused, wperm = ost.compress(x)
+        assert used[t] == wused, t
+        assert out[offs[t]:offs[t + 1]].cpu().numpy().tobytes() == want, t
+        assert np.array_equal(perms[t].cpu().numpy().astype(np.uint32), wperm), t
+        recs.append(want)
+    assert sum(1 for u in used if u == lcp.METHOD_T) >= 20
+    dplan = lcp.Plan(EB, lcp.EB_REL_GLOBAL, multi_frame=True, batch_size=batch, block_log2=4,
+                     max_particles=n)
+    dec = dplan.decompress(out, offs)
+    dst = O.Stream(O.EB_REL_GLOBAL, EB, batch_size=batch, block_log2=4, max_n=n)
+    for t in range(len(xs)):
+        w = dst.decompress(recs[t])
+        assert all(bits_equal(dec[t][f].cpu().numpy(), w[f]) for f in range(3)), t
