@@ -276,7 +276,20 @@ lcp_status lcp_kernel_timer_read(lcp_plan_t plan, double* total_ms, uint64_t* la
  * Each result is exactly what a standalone plan with the same parameters gives
  * for the same sequence of calls.  The caller owns every frame, record and
  * output buffer and keeps it alive until the request's lcp_server_wait
- * returns. */
+ * returns.
+ *
+ * Continuous batching (batch_frames > 0): requests of different streams that
+ * are admissible together and use the temporal path (Sec. 5) -- compress
+ * requests whose stream's LCP-FSM state (Sec. 7.2) or method sends the frame to
+ * LCP-T, decompress requests of LCP-T records -- share one set of launches:
+ * one residual (or decode) launch and one coding (or reconstruction) launch
+ * for up to batch_frames requests holding up to batch_particles particles in
+ * all, on a batch scratch allocated per (fields, chunk size) when the first
+ * such stream opens (counted against hbm_budget_bytes).  Records, frames and
+ * stream state are the same as without merging: a merged request whose LCP-T
+ * record comes out larger than the stream's last LCP-S record, or whose record
+ * turns out to be LCP-S, is put back at the front of the queue and runs
+ * alone. */
 typedef struct lcp_server_s* lcp_server_t;
 
 typedef struct {
@@ -284,6 +297,10 @@ typedef struct {
   uint64_t scratch_bytes;    /* arena for in-flight requests' scratch (> 0) */
   int workers;               /* requests in flight at once, 1..16 */
   int device;                /* HIP device ordinal */
+  int batch_frames;          /* most requests one merged launch takes: 0 (no merging)
+                                or 2..64 */
+  uint64_t batch_particles;  /* most particles of one merged launch (> 0 when
+                                batch_frames > 0, < 2^32) */
 } lcp_server_params;
 
 enum { LCP_REQ_COMPRESS = 1, LCP_REQ_DECOMPRESS = 2 };
@@ -308,6 +325,7 @@ typedef struct {
   int method;          /* compress: LCP_METHOD_S or LCP_METHOD_T */
   uint64_t bytes;      /* compress: record bytes; decompress: particles decoded */
   uint64_t t_submit_ns, t_start_ns, t_end_ns; /* steady clock: submitted, admitted, done */
+  int group;           /* requests in the launch set that finished this one (1: alone) */
 } lcp_result;
 
 /* Create a server: allocates the arena and starts the workers.
@@ -331,6 +349,12 @@ lcp_status lcp_server_submit(lcp_server_t server, const lcp_request* request, ui
 
 /* Block until the request is done and return its result (once per ticket). */
 lcp_status lcp_server_wait(lcp_server_t server, uint64_t ticket, lcp_result* result);
+
+/* Counters since creation: merged launch sets run, requests they finished,
+ * requests they put back to run alone (any pointer may be NULL).
+ * Errors: LCP_ERR_ARG (no server). */
+lcp_status lcp_server_counts(lcp_server_t server, uint64_t* merged_launches,
+                             uint64_t* merged_requests, uint64_t* requeued);
 
 #ifdef __cplusplus
 }

@@ -1279,6 +1279,20 @@ __global__ __launch_bounds__(kThreads) void k_t_recon_chain(const int32_t* q_ref
   if (bad) atomicOr(err, kErrCorrupt);
 }
 
+// Record r of a merged launch (bytes [offs[r], offs[r+1]) of src) to its own
+// destination tab[2r] when it fits the capacity tab[2r + 1]; blockIdx.y
+// strides over its words.
+__global__ void k_scatter_records(const unsigned long long* offs, const uint8_t* src,
+                                  const uint64_t* tab, int R) {
+  const int r = blockIdx.x;
+  const uint64_t lo = offs[r], size = offs[r + 1] - lo;
+  if (size > tab[2 * r + 1]) return;
+  uint32_t* d = reinterpret_cast<uint32_t*>((uintptr_t)tab[2 * r]);
+  const uint32_t* s = reinterpret_cast<const uint32_t*>(src + lo);
+  const uint64_t words = size / 4, stride = (uint64_t)gridDim.y * blockDim.x;
+  for (uint64_t w = (uint64_t)blockIdx.y * blockDim.x + threadIdx.x; w < words; w += stride) d[w] = s[w];
+}
+
 // Copies the first min(size, stage) bytes (whole words) of every record into a
 // staging array, one workgroup per record.
 __global__ void k_gather_headers(const uint64_t* tab, int stage, uint8_t* dst) {
@@ -1575,6 +1589,11 @@ void launch_t_recon_chain(const int32_t* q_ref, int F, uint64_t n, const GridDev
     }
   launch_timed("t_recon", n * (per + 4ull * F + (q_last ? 4ull * F : 0)), k_t_recon_chain, grid_for(vec ? n / 4 : n, kThreads * 2, 1u << 16), kThreads, 0, s,
                q_ref, F, n, g, out, J, q_last, err, vec);
+}
+
+void launch_scatter_records(const unsigned long long* offs, const uint8_t* src, const uint64_t* tab,
+                            int R, hipStream_t s) {
+  if (R > 0) k_scatter_records<<<dim3(R, 16), kThreads, 0, s>>>(offs, src, tab, R);
 }
 
 void launch_gather_headers(const uint64_t* tab, int nrec, int stage, uint8_t* dst, hipStream_t s) {

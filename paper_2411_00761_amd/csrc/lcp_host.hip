@@ -214,6 +214,7 @@ struct lcp_plan_s {
   int untested = 0;
   uint64_t last_s = 0;
   bool have_last_s = false;
+  bool dec_last_t = false;  // the last record decoded was LCP-T
 
   // launch shape of the batch encode kernels (tuned, or the defaults) and the
   // graphs captured for batches of LCP-S frames, keyed by their launch shape
@@ -1670,6 +1671,7 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
   if (multi) {
     P->dprev = sp;
     P->danchor = sa;
+    P->dec_last_t = nf > 0 && H[nf - 1].mode == 1;
   }
   return LCP_OK;
 }
@@ -2212,6 +2214,7 @@ lcp_status lcp_plan_reset(lcp_plan_t plan) {
   plan->anchor = RefState();
   plan->dprev = RefState();
   plan->danchor = RefState();
+  plan->dec_last_t = false;
   plan->have_eb = false;
   plan->seq = 0;
   plan->fsm_state = kFsmS1;
@@ -2426,6 +2429,263 @@ lcp_status lcp_kernel_timer_read(lcp_plan_t plan, double* total_ms, uint64_t* la
 
 }  // extern "C"
 
+
+// ================================================================== served form: merged launches
+// A server merges the temporal requests of different streams into one set of
+// launches on a batch plan (serve_batch scratch for up to RB frames).  The
+// records and stream states are exactly those of each stream's own calls.
+namespace lcp {
+
+lcp_status serve_batch_create(int F, int chunk_log2, int frames, uint64_t particles, int device,
+                              lcp_plan_s** out) {
+  lcp_params p{};
+  p.eb_mode = LCP_EB_ABS;
+  p.eb = 1.0;
+  p.n_fields = F;
+  p.chunk_log2 = chunk_log2;
+  p.max_particles = particles;
+  p.max_batch_particles = particles;
+  p.max_batch_frames = frames;
+  p.device = device;
+  lcp_plan_s* P = nullptr;
+  lcp_status st = plan_setup(&p, nullptr, 0, &P);
+  if (st) return st;
+  P->serve_batch = true;
+  st = alloc_plan(P);
+  if (st) {
+    free_plan(P);
+    return st;
+  }
+  *out = P;
+  return LCP_OK;
+}
+
+size_t serve_batch_bytes(lcp_plan_s* B) { return B->scratch_bytes; }
+int serve_batch_fields(lcp_plan_s* B) { return B->F; }
+int serve_batch_frames(lcp_plan_s* B) { return B->RB; }
+uint64_t serve_batch_particles(lcp_plan_s* B) { return B->NB; }
+int plan_fields(lcp_plan_s* P) { return P->F; }
+int plan_chunk_log2(lcp_plan_s* P) { return P->chunk_log2; }
+bool plan_decoding_t(lcp_plan_s* P) { return P->p.multi_frame && P->dec_last_t; }
+
+// Whether the stream's next compress request can join a merged launch: its
+// frame will be coded by LCP-T (LCP-FSM in its T state, or forced T) against a
+// resident reference of the same size, so that the merged launch decides it
+// (kept if no larger than the last LCP-S record) as the stream's own call would.
+bool serve_t_eligible(lcp_plan_s* P, const lcp_frame_in& fr) {
+  if (!P->p.multi_frame || fr.n == 0 || fr.n > P->N) return false;
+  if (fr.method == LCP_METHOD_S || fr.method < 0 || fr.method > 2) return false;
+  if (fr.method == LCP_METHOD_AUTO && (P->fsm_state != kFsmT || !P->have_last_s)) return false;
+  for (int f = 0; f < P->F; f++)
+    if (!fr.fields[f]) return false;
+  return reference_for(P, fr.n) != nullptr && free_q(P, -1) >= 0;
+}
+
+lcp_status serve_t_compress(lcp_plan_s* B, int K, lcp_plan_s* const* plans,
+                            const lcp_frame_in* frames, void* const* outs, const uint64_t* caps,
+                            bool* done, uint64_t* sizes, hipStream_t s) {
+  const int F = B->F;
+  if (K < 1 || K > B->RB) return LCP_ERR_ARG;
+  TimerScope ts(B);
+  std::vector<RefState> refs(K);
+  std::vector<int> qsel(K);
+  uint64_t off = 0, bytes = 0;
+  uint32_t blocks = 0;
+  for (int i = 0; i < K; i++) {
+    lcp_plan_s* P = plans[i];
+    const lcp_frame_in& fr = frames[i];
+    done[i] = false;
+    const RefState* ref = reference_for(P, fr.n);
+    if (P->F != F || P->chunk_log2 != B->chunk_log2 || !ref) return LCP_ERR_ARG;
+    refs[i] = *ref;
+    qsel[i] = free_q(P, -1);
+    TFrameDev& t = B->tfr_host[i];
+    memset(&t, 0, sizeof(t));
+    for (int f = 0; f < F; f++) t.x[f] = fr.fields[f];
+    t.perm = P->ppool[ref->perm];
+    t.q_ref = P->qpool[ref->q];
+    t.q_new = P->qpool[qsel[i]];
+    t.v8 = B->v_byte + (uint64_t)F * off;
+    t.esc = B->v_slot + (uint64_t)F * off;
+    t.err = reinterpret_cast<uint32_t*>(B->sret_dev + i);
+    t.n = fr.n;
+    t.vec = fr.n % 4 == 0;
+    t.g = t_grid(*ref, F);
+    B->spre_host[i] = blocks;
+    blocks += t_multi_blocks(fr.n, t.vec);
+    off += fr.n;
+    bytes += fr.n * (4 + 12ull * F);
+  }
+  B->spre_host[K] = blocks;
+  if (off > B->NB) return LCP_ERR_ARG;
+  lcp_status st = upload(B->tfr_host, B->tfr_dev, sizeof(TFrameDev) * K, s);
+  if (!st) st = upload(B->spre_host, B->spre_dev, sizeof(uint32_t) * (K + 1), s);
+  if (st) return st;
+  unsigned long long* offs = B->sret_dev + K;
+  uint32_t* launch_err = reinterpret_cast<uint32_t*>(B->sret_dev + 2 * K + 1);
+  launch_fill_u32(reinterpret_cast<uint32_t*>(B->sret_dev), 2 * (2 * (uint64_t)K + 2), 0u, s);
+  const bool fused = B->fuse_skip == 0 && B->chunk_log2 >= 6 && B->chunk_log2 <= 10;
+  if (B->fuse_skip > 0) B->fuse_skip = B->fuse_skip > K ? B->fuse_skip - K : 0;
+  launch_t_resid_multi(B->tfr_dev, B->spre_dev, blocks, K, F, B->hist_part, B->hist_max,
+                       kServeCopies, fused ? B->work : nullptr, bytes, s);
+  EncBuild EB;
+  EB.R = K;
+  EB.fused = fused;
+  off = 0;
+  for (int i = 0; i < K; i++) {
+    const uint64_t n = frames[i].n;
+    EncRec& rc = B->erec_host[i];
+    memset(&rc, 0, sizeof(rc));
+    rc.h = make_hdr(1, F, 0, B->chunk_log2, F, n, plans[i]->seq, refs[i].seq, refs[i].grid);
+    rc.a0 = (uint32_t)EB.NA;
+    for (int f = 0; f < F; f++) {
+      const uint64_t a = (uint64_t)i * F + f;
+      if ((st = enc_add(B, EB, ArrIn{B->v_byte + (uint64_t)F * off + (uint64_t)f * n, 0, nullptr, n,
+                                     B->v_slot + (uint64_t)F * off + (uint64_t)f * n},
+                        n, i, (int)(a * kServeCopies), kServeCopies)))
+        return st;
+    }
+    off += n;
+  }
+  if ((st = enc_launch(B, EB, B->rec_tmp, B->rec_tmp_cap, true, s, launch_err, offs, nullptr,
+                       reinterpret_cast<uint32_t*>(B->sret_dev), 2)))
+    return st;
+  for (int i = 0; i < K; i++) {
+    B->sdst_host[2 * i] = (uint64_t)(uintptr_t)outs[i];
+    B->sdst_host[2 * i + 1] = caps[i];
+  }
+  if ((st = upload(B->sdst_host, B->sdst_dev, sizeof(uint64_t) * 2 * K, s))) return st;
+  launch_scatter_records(offs, B->rec_tmp, B->sdst_dev, K, s);
+  HIP_OK(hipMemcpyAsync(B->sret_host, B->sret_dev, 8 * (2 * (size_t)K + 2), hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  if (g_timer_plan == B) timer_collect(B);
+  const uint32_t lerr = (uint32_t)(B->sret_host[2 * K + 1] & 0xFFFFFFFFull);
+  if (lerr & kErrCorrupt) return LCP_ERR_DEVICE;
+  for (int i = 0; i < K; i++)
+    if ((uint32_t)(B->sret_host[i] & 0xFFFFFFFFull) & kErrRebuild) {
+      fused_fallback(B, s);
+      break;
+    }
+  for (int i = 0; i < K; i++) {
+    lcp_plan_s* P = plans[i];
+    const uint32_t flags = (uint32_t)(B->sret_host[i] & 0xFFFFFFFFull);
+    const uint64_t size = B->sret_host[K + i + 1] - B->sret_host[K + i];
+    if (flags || (lerr & kErrCapacity) || size > caps[i]) continue;
+    if (frames[i].method == LCP_METHOD_AUTO && size > P->last_s) continue;
+    // committed as the stream's own call commits a kept temporal frame
+    if (frames[i].method == LCP_METHOD_AUTO) fsm_update(P, LCP_DECIDE_T, true, true);
+    RefState r = refs[i];
+    r.seq = P->seq;
+    r.q = qsel[i];
+    P->prev = r;
+    P->seq++;
+    sizes[i] = size;
+    done[i] = true;
+  }
+  return LCP_OK;
+}
+
+lcp_status serve_t_decompress(lcp_plan_s* B, int K, lcp_plan_s* const* plans,
+                              const lcp_blob* blobs, const lcp_frame_out* dsts, bool* done,
+                              uint64_t* n_out, hipStream_t s) {
+  const int F = B->F;
+  if (K < 1 || K > B->RB) return LCP_ERR_ARG;
+  TimerScope ts(B);
+  for (int i = 0; i < K; i++) {
+    done[i] = false;
+    if (!blobs[i].data || ((uintptr_t)blobs[i].data & 3)) return LCP_ERR_ARG;
+    B->blobtab_host[2 * i] = (uint64_t)(uintptr_t)blobs[i].data;
+    B->blobtab_host[2 * i + 1] = blobs[i].size;
+  }
+  lcp_status st = upload(B->blobtab_host, B->blobtab_dev, 16ull * K, s);
+  if (st) return st;
+  launch_gather_headers(B->blobtab_dev, K, kHdrStage, B->hdr_dev, s);
+  HIP_OK(hipMemcpyAsync(B->hdr_host, B->hdr_dev, (size_t)kHdrStage * K, hipMemcpyDeviceToHost, s));
+  HIP_OK(hipStreamSynchronize(s));
+  std::vector<ParsedHdr> H(K);
+  std::vector<int> dq(K, -1), take;
+  uint64_t off = 0, bytes = 0;
+  uint32_t blocks = 0;
+  int A = 0;
+  for (int i = 0; i < K; i++) {
+    lcp_plan_s* P = plans[i];
+    ParsedHdr& h = H[i];
+    if (parse_header(B->hdr_host + (size_t)kHdrStage * i, blobs[i].size, &h)) continue;
+    if (h.mode != 1 || h.F != F || h.cl != B->chunk_log2 || P->F != F || h.n > P->N ||
+        h.n > dsts[i].capacity || off + h.n > B->NB)
+      continue;
+    bool fields = true;
+    for (int f = 0; f < F; f++) fields = fields && dsts[i].fields[f];
+    if (!fields) continue;
+    int refq = -1;
+    if (P->dprev.valid && P->dprev.seq == h.ref_seq && P->dprev.n == h.n) refq = P->dprev.q;
+    else if (P->danchor.valid && P->danchor.seq == h.ref_seq && P->danchor.n == h.n) refq = P->danchor.q;
+    if (refq < 0) continue;
+    for (int q = 0; q < 3; q++)
+      if (!(P->dprev.valid && P->dprev.q == q) && !(P->danchor.valid && P->danchor.q == q)) {
+        dq[i] = q;
+        break;
+      }
+    if (dq[i] < 0) continue;
+    const uint8_t* rec = reinterpret_cast<const uint8_t*>(blobs[i].data);
+    for (int f = 0; f < F; f++) {
+      DecArr& d = B->arrtab_host[A++];
+      d.data = rec + h.aoff[f];
+      d.nbytes = h.anb[f];
+      d.n = h.an[f];
+      d.coder = h.coder[f];
+      d.param = h.param[f];
+      d.used = h.used[f];
+      d.out = B->dres8 + (uint64_t)F * off + (uint64_t)f * h.n;
+      d.esc = reinterpret_cast<int32_t*>(dsts[i].fields[f]);
+      d.mode = 4;
+      d.limit = 1ull << 25;
+      bytes += h.anb[f] + 4 * h.an[f];
+    }
+    TReconDev& t = B->trc_host[take.size()];
+    memset(&t, 0, sizeof(t));
+    t.q_ref = P->dqpool[refq];
+    t.q_new = P->dqpool[dq[i]];
+    t.r8 = reinterpret_cast<const int8_t*>(B->dres8 + (uint64_t)F * off);
+    for (int f = 0; f < F; f++) {
+      t.out[f] = dsts[i].fields[f];
+      t.m[f] = h.m[f];
+      t.eb_q[f] = h.eb_q[f];
+    }
+    t.n = h.n;
+    B->spre_host[take.size()] = blocks;
+    blocks += (uint32_t)((h.n + kSeg1k - 1) / kSeg1k);
+    off += h.n;
+    take.push_back(i);
+  }
+  if (take.empty()) return LCP_OK;
+  const int KT = (int)take.size();
+  B->spre_host[KT] = blocks;
+  clear_err(B, s);
+  if ((st = decode_arrays(B, 0, A, B->chunk_log2, bytes, s))) return st;
+  if ((st = upload(B->trc_host, B->trc_dev, sizeof(TReconDev) * KT, s))) return st;
+  if ((st = upload(B->spre_host, B->spre_dev, sizeof(uint32_t) * (KT + 1), s))) return st;
+  launch_t_recon_multi(B->trc_dev, B->spre_dev, blocks, KT, F, B->err, off * 16ull * F, s);
+  if ((st = read_ret(B, 1, s))) return st;
+  if (g_timer_plan == B) timer_collect(B);
+  if (host_err(B) & kErrCorrupt) return LCP_OK;  // each goes its own way, which reports it
+  for (int j = 0; j < KT; j++) {
+    const int i = take[j];
+    lcp_plan_s* P = plans[i];
+    RefState r;
+    r.valid = true;
+    r.seq = H[i].seq;
+    r.n = H[i].n;
+    r.q = dq[i];
+    P->dprev = r;
+    P->dec_last_t = true;
+    n_out[i] = H[i].n;
+    done[i] = true;
+  }
+  return LCP_OK;
+}
+
+}  // namespace lcp
 
 // ================================================================== no-allocation entry point
 // lcp_compress_static runs the single-frame LCP-S path of lcp_compress on

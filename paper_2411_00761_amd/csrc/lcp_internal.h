@@ -159,6 +159,36 @@ inline void launch_timed(const char* name, uint64_t bytes, K kernel, dim3 grid, 
     kernel<<<grid, block, shm, s>>>(args...);
 }
 
+// ---- lcp_host.hip: the server's merged temporal launches ----
+// A batch plan holds the scratch of one merged launch: up to `frames` temporal
+// frames of different streams with F fields and chunk size chunk_log2, and
+// `particles` particles in all.
+lcp_status serve_batch_create(int F, int chunk_log2, int frames, uint64_t particles, int device,
+                              lcp_plan_s** out);
+size_t serve_batch_bytes(lcp_plan_s* B);
+int serve_batch_fields(lcp_plan_s* B);
+int serve_batch_frames(lcp_plan_s* B);
+uint64_t serve_batch_particles(lcp_plan_s* B);
+int plan_fields(lcp_plan_s* P);
+int plan_chunk_log2(lcp_plan_s* P);
+// Whether the stream's last decoded record was LCP-T (its next one likely is).
+bool plan_decoding_t(lcp_plan_s* P);
+// Whether a compress request of the stream can join a merged launch (its frame
+// goes to LCP-T against a resident reference whatever the size comparison).
+bool serve_t_eligible(lcp_plan_s* P, const lcp_frame_in& fr);
+// K requests of K different streams (plans[i], its next frame or record): one
+// residual (or decode) launch, one coding (or reconstruction) launch for all.
+// done[i]: request i is finished exactly as the stream's own lcp_compress /
+// lcp_decompress would have finished it (stream state committed; size or
+// particle count in sizes / n_out); otherwise nothing of its stream changed
+// and it must take its own call.
+lcp_status serve_t_compress(lcp_plan_s* B, int K, lcp_plan_s* const* plans,
+                            const lcp_frame_in* frames, void* const* outs, const uint64_t* caps,
+                            bool* done, uint64_t* sizes, hipStream_t s);
+lcp_status serve_t_decompress(lcp_plan_s* B, int K, lcp_plan_s* const* plans,
+                              const lcp_blob* blobs, const lcp_frame_out* dsts, bool* done,
+                              uint64_t* n_out, hipStream_t s);
+
 // ---- lcp_host.hip: plans whose scratch is bound per call (the server) ----
 // A plan with its stream state but no scratch; the block-size search, if asked
 // for, runs on temporary scratch.  Before each call, plan_bind points the plan
@@ -338,6 +368,10 @@ void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 // tab: nrec (device pointer, byte size) pairs; dst: nrec * stage bytes.
 void launch_gather_headers(const uint64_t* tab, int nrec, int stage, uint8_t* dst, hipStream_t s);
 void launch_copy_perm(const uint32_t* src, uint32_t* dst, uint64_t n, hipStream_t s);
+// Record r (src bytes [offs[r], offs[r+1])) to the device pointer tab[2r] when
+// its size is at most tab[2r + 1].
+void launch_scatter_records(const unsigned long long* offs, const uint8_t* src, const uint64_t* tab,
+                            int R, hipStream_t s);
 
 // ---- kernels_codec.hip ----
 // Workgroups per array in the histogram pass (at most); their counts meet in

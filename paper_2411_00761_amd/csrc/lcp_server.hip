@@ -9,7 +9,19 @@
 // in submission order), and the arena has room for its scratch.  Requests of
 // different streams therefore overlap on the device, and the memory a finished
 // request releases admits the next one.
+//
+// Continuous batching: with batch plans enabled, the temporal requests that
+// are admissible together -- compress requests whose stream's next frame goes
+// to LCP-T, decompress requests of streams with the same fields and chunk size
+// -- are merged into one set of launches on a batch plan (one residual or
+// decode launch, one coding or reconstruction launch for all of them) instead
+// of one set per request.  A merged request finishes exactly as its stream's
+// own call would; one the merged launch cannot finish (its temporal record is
+// larger than the last spatial one, or it is a spatial record) goes back to
+// the front of the queue and takes its own call.
+#include <algorithm>
 #include <chrono>
+#include <memory>
 #include <condition_variable>
 #include <deque>
 #include <map>
@@ -41,6 +53,7 @@ struct ServedStream {
 struct Ticket {
   lcp_request req;
   lcp_result res;
+  bool solo = false;  // takes its own call (a merged launch could not finish it)
   // recorded on req.after at submit: the worker's stream waits for it, so the
   // request reads inputs and overwrites outputs only after the caller's
   // earlier work on them
@@ -86,8 +99,17 @@ struct Arena {
 
 }  // namespace
 
+// The scratch of merged launches for streams of one (fields, chunk size).
+struct BatchSlot {
+  int F = 0, cl = 0;
+  lcp_plan_s* plan = nullptr;
+  bool busy = false;
+};
+
 struct lcp_server_s {
   lcp_server_params p{};
+  std::deque<BatchSlot> batches;  // stable addresses
+  uint64_t merged_launches = 0, merged_requests = 0, requeued = 0;
   void* arena_mem = nullptr;
   Arena arena;
   size_t state_used = 0;
@@ -105,11 +127,42 @@ struct lcp_server_s {
 
 namespace {
 
-// Next admissible request (lock held): the first pending one whose stream is
-// idle and has no earlier pending request; memory is admitted strictly in
-// order, so a large request is not starved by smaller ones behind it.
-bool pick(lcp_server_s* S, uint64_t* ticket, size_t* off) {
+BatchSlot* batch_for(lcp_server_s* S, const Ticket& t) {
+  if (t.solo) return nullptr;
+  lcp_plan_s* P = S->streams[t.req.stream].plan;
+  for (BatchSlot& b : S->batches)
+    if (b.F == plan_fields(P) && b.cl == plan_chunk_log2(P)) return &b;
+  return nullptr;
+}
+
+// Particles a request brings into a merged launch (at most).
+uint64_t particles_of(const Ticket& t) {
+  return t.req.kind == LCP_REQ_COMPRESS ? t.req.frame.n : t.req.dst.capacity;
+}
+
+bool mergeable(lcp_server_s* S, const Ticket& t, BatchSlot* b) {
+  if (!b || batch_for(S, t) != b) return false;
+  if (t.req.kind == LCP_REQ_COMPRESS) return serve_t_eligible(S->streams[t.req.stream].plan, t.req.frame);
+  // decompress: whether the record is temporal shows once its header is read;
+  // a stream whose last record was temporal most likely sends another
+  return plan_decoding_t(S->streams[t.req.stream].plan);
+}
+
+// Next work (lock held), taken in arrival order among requests whose stream
+// is idle and has no earlier pending request.  The first such request that
+// can be merged leads a group, joined by the further ones of the same kind
+// and batch scratch, up to its frame and particle capacity; one that can be
+// merged while its batch scratch is in use waits for it.  The first request
+// that cannot be merged runs alone (single) on scratch from the arena; memory
+// is admitted strictly in order, so a large request is not starved by smaller
+// ones behind it.
+bool pick(lcp_server_s* S, std::vector<uint64_t>* group, BatchSlot** slot, uint64_t* single,
+          size_t* off) {
   std::vector<char> blocked(S->streams.size(), 0);
+  group->clear();
+  *slot = nullptr;
+  int kind = 0;
+  uint64_t parts = 0;
   for (auto it = S->pending.begin(); it != S->pending.end(); ++it) {
     const Ticket& t = S->tickets[*it];
     const int sid = t.req.stream;
@@ -117,13 +170,100 @@ bool pick(lcp_server_s* S, uint64_t* ticket, size_t* off) {
     blocked[sid] = 1;
     ServedStream& st = S->streams[sid];
     if (st.busy) continue;
-    if (!S->arena.alloc(st.scratch, off)) return false;
-    st.busy = true;
-    *ticket = *it;
-    S->pending.erase(it);
-    return true;
+    BatchSlot* b = batch_for(S, t);
+    const bool m = b && mergeable(S, t, b) && particles_of(t) <= serve_batch_particles(b->plan);
+    if (group->empty()) {
+      if (m && b->busy) continue;  // waits for its batch scratch
+      if (m) {
+        *slot = b;
+        kind = t.req.kind;
+        parts = particles_of(t);
+        group->push_back(*it);
+        continue;
+      }
+      if (!S->arena.alloc(st.scratch, off)) return false;
+      st.busy = true;
+      *single = *it;
+      S->pending.erase(it);
+      return true;
+    }
+    if ((int)group->size() >= serve_batch_frames((*slot)->plan)) break;
+    if (!m || b != *slot || t.req.kind != kind) continue;
+    if (parts + particles_of(t) > serve_batch_particles(b->plan)) continue;
+    parts += particles_of(t);
+    group->push_back(*it);
   }
-  return false;
+  if (group->empty()) return false;
+  for (uint64_t id : *group) {
+    S->streams[S->tickets[id].req.stream].busy = true;
+    S->pending.erase(std::find(S->pending.begin(), S->pending.end(), id));
+  }
+  (*slot)->busy = true;
+  return true;
+}
+
+// A merged launch of the group's requests on the worker's stream; the ones it
+// finished complete, the others go back to the front of the queue in order.
+void run_group(lcp_server_s* S, const std::vector<uint64_t>& group, BatchSlot* slot,
+               hipStream_t hs) {
+  const int K = (int)group.size();
+  std::vector<lcp_plan_s*> plans(K);
+  std::vector<lcp_frame_in> frames(K);
+  std::vector<void*> outs(K);
+  std::vector<uint64_t> caps(K), sizes(K, 0), nout(K, 0);
+  std::vector<lcp_blob> blobs(K);
+  std::vector<lcp_frame_out> dsts(K);
+  std::unique_ptr<bool[]> done(new bool[K]());
+  int kind = 0;
+  bool ok = true;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    const uint64_t now = now_ns();
+    for (int i = 0; i < K; i++) {
+      Ticket& t = S->tickets[group[i]];
+      t.res.t_start_ns = now;
+      kind = t.req.kind;
+      plans[i] = S->streams[t.req.stream].plan;
+      frames[i] = t.req.frame;
+      outs[i] = t.req.out;
+      caps[i] = t.req.out_cap;
+      blobs[i] = t.req.blob;
+      dsts[i] = t.req.dst;
+      if (t.ready && hipStreamWaitEvent(hs, t.ready, 0) != hipSuccess) ok = false;
+    }
+  }
+  lcp_status st = LCP_ERR_DEVICE;
+  if (ok)
+    st = kind == LCP_REQ_COMPRESS
+             ? serve_t_compress(slot->plan, K, plans.data(), frames.data(), outs.data(), caps.data(),
+                                done.get(), sizes.data(), hs)
+             : serve_t_decompress(slot->plan, K, plans.data(), blobs.data(), dsts.data(), done.get(),
+                                  nout.data(), hs);
+  const uint64_t end = now_ns();
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->merged_launches++;
+    for (int i = K - 1; i >= 0; i--) {
+      Ticket& t = S->tickets[group[i]];
+      S->streams[t.req.stream].busy = false;
+      if (st == LCP_OK && done[i]) {
+        t.res.status = LCP_OK;
+        t.res.method = kind == LCP_REQ_COMPRESS ? LCP_METHOD_T : 0;
+        t.res.bytes = kind == LCP_REQ_COMPRESS ? sizes[i] : nout[i];
+        t.res.t_end_ns = end;
+        t.res.group = K;
+        if (t.ready) (void)hipEventDestroy(t.ready);
+        t.ready = nullptr;
+        t.done = true;
+        S->merged_requests++;
+      } else {
+        t.solo = true;  // back to the front of the queue, in order
+        S->pending.push_front(group[i]);
+        S->requeued++;
+      }
+    }
+    slot->busy = false;
+  }
 }
 
 void run_request(lcp_plan_s* plan, const lcp_request& rq, hipStream_t hs, lcp_result* res) {
@@ -152,11 +292,21 @@ void worker_main(lcp_server_s* S) {
   for (;;) {
     uint64_t tk = 0;
     size_t off = 0;
+    std::vector<uint64_t> group;
+    BatchSlot* slot = nullptr;
     {
       std::unique_lock<std::mutex> lk(S->mu);
       if (init != LCP_OK) S->worker_error = init;
-      S->cv_work.wait(lk, [&] { return S->stop || (init == LCP_OK && pick(S, &tk, &off)); });
-      if (S->stop && tk == 0) break;
+      S->cv_work.wait(lk, [&] {
+        return S->stop || (init == LCP_OK && pick(S, &group, &slot, &tk, &off));
+      });
+      if (S->stop && tk == 0 && group.empty()) break;
+    }
+    if (!group.empty()) {
+      run_group(S, group, slot, hs);
+      S->cv_done.notify_all();
+      S->cv_work.notify_all();
+      continue;
     }
     Ticket* t;
     lcp_plan_s* plan;
@@ -167,6 +317,7 @@ void worker_main(lcp_server_s* S) {
       t->res.t_start_ns = now_ns();
     }
     lcp_result res = t->res;
+    res.group = 1;
     if (t->ready && hipStreamWaitEvent(hs, t->ready, 0) != hipSuccess) {
       res.status = LCP_ERR_DEVICE;
     } else {
@@ -202,7 +353,9 @@ lcp_status lcp_server_create(const lcp_server_params* params, lcp_server_t* out)
   *out = nullptr;
   const lcp_server_params& p = *params;
   if (p.workers < 1 || p.workers > 16 || p.scratch_bytes == 0 ||
-      (p.hbm_budget_bytes && p.scratch_bytes > p.hbm_budget_bytes))
+      (p.hbm_budget_bytes && p.scratch_bytes > p.hbm_budget_bytes) || p.batch_frames < 0 ||
+      p.batch_frames > 64 || p.batch_frames == 1 || p.batch_particles > 0xFFFFFFFFull ||
+      (p.batch_frames > 0 && p.batch_particles == 0))
     return LCP_ERR_ARG;
   if (hipSetDevice(p.device) != hipSuccess) return LCP_ERR_DEVICE;
   lcp_server_s* S = new lcp_server_s();
@@ -244,6 +397,9 @@ void lcp_server_destroy(lcp_server_t S) {
   S->cv_work.notify_all();
   for (auto& th : S->workers) th.join();
   for (auto& st : S->streams) lcp_plan_destroy(st.plan);
+  for (auto& b : S->batches) lcp_plan_destroy(b.plan);
+  for (auto& kv : S->tickets)
+    if (kv.second.ready) (void)hipEventDestroy(kv.second.ready);
   if (S->arena_mem) (void)hipFree(S->arena_mem);
   delete S;
 }
@@ -265,6 +421,29 @@ lcp_status lcp_server_open_stream(lcp_server_t S, const lcp_params* params,
     return LCP_ERR_BUDGET;
   }
   S->state_used += state;
+  if (S->p.batch_frames > 0) {
+    bool have = false;
+    for (const BatchSlot& b : S->batches)
+      have |= b.F == plan_fields(plan) && b.cl == plan_chunk_log2(plan);
+    if (!have) {
+      BatchSlot b;
+      b.F = plan_fields(plan);
+      b.cl = plan_chunk_log2(plan);
+      st = serve_batch_create(b.F, b.cl, S->p.batch_frames, S->p.batch_particles, S->p.device,
+                              &b.plan);
+      if (st == LCP_OK && S->p.hbm_budget_bytes &&
+          S->state_used + serve_batch_bytes(b.plan) + S->p.scratch_bytes > S->p.hbm_budget_bytes)
+        st = LCP_ERR_BUDGET;
+      if (st) {
+        if (b.plan) lcp_plan_destroy(b.plan);
+        S->state_used -= state;
+        lcp_plan_destroy(plan);
+        return st;
+      }
+      S->state_used += serve_batch_bytes(b.plan);
+      S->batches.push_back(b);
+    }
+  }
   ServedStream ss;
   ss.plan = plan;
   ss.scratch = scratch;
@@ -311,6 +490,16 @@ lcp_status lcp_server_wait(lcp_server_t S, uint64_t ticket, lcp_result* res) {
   if (!t.done) return S->worker_error;
   *res = t.res;
   S->tickets.erase(ticket);
+  return LCP_OK;
+}
+
+lcp_status lcp_server_counts(lcp_server_t S, uint64_t* merged_launches, uint64_t* merged_requests,
+                             uint64_t* requeued) {
+  if (!S) return LCP_ERR_ARG;
+  std::lock_guard<std::mutex> lk(S->mu);
+  if (merged_launches) *merged_launches = S->merged_launches;
+  if (merged_requests) *merged_requests = S->merged_requests;
+  if (requeued) *requeued = S->requeued;
   return LCP_OK;
 }
 

@@ -27,7 +27,7 @@ EXPORTED = ["lcp_plan", "lcp_plan_destroy", "lcp_plan_reset", "lcp_plan_block_lo
             "lcp_kernel_timer_read", "lcp_server_create", "lcp_server_destroy",
             "lcp_server_open_stream", "lcp_server_submit", "lcp_server_wait",
             "lcp_scratch_bytes", "lcp_compress_static", "lcp_plan_set_tuning",
-            "lcp_plan_get_tuning", "lcp_plan_autotune"]
+            "lcp_plan_get_tuning", "lcp_plan_autotune", "lcp_server_counts"]
 REQ_COMPRESS, REQ_DECOMPRESS = 1, 2
 
 
@@ -112,7 +112,8 @@ def frame_out_table(outs, F):
 
 class lcp_server_params(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_uint64), ("scratch_bytes", C.c_uint64),
-                ("workers", C.c_int), ("device", C.c_int)]
+                ("workers", C.c_int), ("device", C.c_int), ("batch_frames", C.c_int),
+                ("batch_particles", C.c_uint64)]
 
 
 class lcp_request(C.Structure):
@@ -123,7 +124,8 @@ class lcp_request(C.Structure):
 
 class lcp_result(C.Structure):
     _fields_ = [("status", C.c_int), ("method", C.c_int), ("bytes", C.c_uint64),
-                ("t_submit_ns", C.c_uint64), ("t_start_ns", C.c_uint64), ("t_end_ns", C.c_uint64)]
+                ("t_submit_ns", C.c_uint64), ("t_start_ns", C.c_uint64), ("t_end_ns", C.c_uint64),
+                ("group", C.c_int)]
 
 
 _lib = None
@@ -168,6 +170,8 @@ def lib():
                                              C.POINTER(C.c_int)]
         L.lcp_server_submit.argtypes = [P, C.POINTER(lcp_request), C.POINTER(C.c_uint64)]
         L.lcp_server_wait.argtypes = [P, C.c_uint64, C.POINTER(lcp_result)]
+        L.lcp_server_counts.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
+                                        C.POINTER(C.c_uint64)]
         _lib = L
     return _lib
 
@@ -374,10 +378,11 @@ class Server:
     caller tensors kept alive here until their request is waited for."""
 
     def __init__(self, scratch_bytes: int, workers: int = 4, hbm_budget_bytes: int = 0,
-                 device: int = 0):
+                 device: int = 0, batch_frames: int = 0, batch_particles: int = 0):
         import torch
         self.device = device
-        p = lcp_server_params(hbm_budget_bytes, scratch_bytes, workers, device)
+        p = lcp_server_params(hbm_budget_bytes, scratch_bytes, workers, device, batch_frames,
+                              batch_particles)
         h = C.c_void_p()
         with torch.cuda.device(device):
             _check(lib().lcp_server_create(C.byref(p), C.byref(h)), "lcp_server_create")
@@ -456,4 +461,12 @@ class Server:
         _check(lib().lcp_server_wait(self.h, ticket, C.byref(r)), "lcp_server_wait")
         self._keep.pop(ticket, None)
         return {"status": r.status, "method": r.method, "bytes": r.bytes,
-                "t_submit_ns": r.t_submit_ns, "t_start_ns": r.t_start_ns, "t_end_ns": r.t_end_ns}
+                "t_submit_ns": r.t_submit_ns, "t_start_ns": r.t_start_ns, "t_end_ns": r.t_end_ns,
+                "group": r.group}
+
+    def counts(self) -> dict:
+        """Launch sets run on batch scratch, requests they finished, requests put back."""
+        a, b, c = C.c_uint64(), C.c_uint64(), C.c_uint64()
+        _check(lib().lcp_server_counts(self.h, C.byref(a), C.byref(b), C.byref(c)),
+               "lcp_server_counts")
+        return {"merged_launches": a.value, "merged_requests": b.value, "requeued": c.value}
