@@ -425,13 +425,18 @@ def bench_served(args, torch, lcp, datagen, dev):
             lat.append(time.monotonic() - a)
         return time.monotonic() - t0, lat, sizes_out
 
-    def run_served(arrivals, workers):
+    batch_particles = min(3 * max(sizes), (1 << 32) - 1)
+
+    def run_served(arrivals, workers, batch_frames=0):
         arena = workers * max(lcp.scratch_bytes(max_particles=n) for n in sizes)
-        srv = lcp.Server(arena, workers=workers)
+        srv = lcp.Server(arena, workers=workers, batch_frames=batch_frames,
+                         batch_particles=batch_particles if batch_frames else 0)
         ids = [srv.open_stream(ebs[j], lcp.EB_REL_GLOBAL, batch_size=16, block_log2=ks[j],
                                max_particles=n) for j, n in enumerate(sizes)]
         torch.cuda.synchronize()
         tickets = []
+        if arrivals is None:
+            srv.hold(True)  # back to back: the whole queue is there from the start
         t0 = time.monotonic()
         for i, (j, t, kind) in enumerate(reqs):
             a = t0 + (arrivals[i] if arrivals is not None else 0.0)
@@ -441,38 +446,54 @@ def bench_served(args, torch, lcp, datagen, dev):
                 tickets.append(srv.compress(ids[j], frames[j][t], recs[j]))
             else:
                 tickets.append(srv.decompress(ids[j], recs[j], 0, caps[j], decs[j]))
+        srv.hold(False)
         res = [srv.wait(tk) for tk in tickets]
         wall = max(r["t_end_ns"] for r in res) / 1e9 - t0
         assert all(r["status"] == 0 for r in res), [r for r in res if r["status"]][:3]
         lat = [(r["t_end_ns"] - r["t_submit_ns"]) / 1e9 for r in res]
         sizes_out = [r["bytes"] for r, (_, _, kind) in zip(res, reqs) if kind == "C"]
+        counts = srv.counts()
         srv.close()
-        return wall, lat, sizes_out
+        return wall, lat, sizes_out, counts
 
+    W, BF = args.served_workers, args.served_batch
     run_plain(None)  # warm-up
     plain_wall, _, plain_sizes = run_plain(None)
     cap_rps = len(reqs) / plain_wall
-    served_wall_b2b, _, served_sizes = run_served(None, args.served_workers)
+    served_wall_b2b, _, served_sizes, _ = run_served(None, W)
     assert served_sizes == plain_sizes, "served records differ from the plain form"
-    rate = args.served_load * cap_rps
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
-    p_wall, p_lat, _ = run_plain(arrivals)
-    s_wall, s_lat, _ = run_served(arrivals, args.served_workers)
+    batched_wall_b2b, _, batched_sizes, b2b_counts = run_served(None, W, BF)
+    assert batched_sizes == plain_sizes, "batched served records differ from the plain form"
     tot = float(sum(req_bytes))
     pct = lambda v, q: float(np.percentile(np.asarray(v) * 1e3, q))  # noqa: E731
+    sweep = []
+    for load in args.served_loads:
+        rate = load * cap_rps
+        arrivals = np.cumsum(np.random.default_rng(11).exponential(1.0 / rate, size=len(reqs)))
+        p_wall, p_lat, _ = run_plain(arrivals)
+        s_wall, s_lat, _, _ = run_served(arrivals, W)
+        b_wall, b_lat, _, b_counts = run_served(arrivals, W, BF)
+        sweep.append({"load": load, "arrival_rate_req_per_s": rate,
+                      "plain_p50_ms": pct(p_lat, 50), "plain_p99_ms": pct(p_lat, 99),
+                      "served_p50_ms": pct(s_lat, 50), "served_p99_ms": pct(s_lat, 99),
+                      "batched_p50_ms": pct(b_lat, 50), "batched_p99_ms": pct(b_lat, 99),
+                      "plain_GBps": tot / p_wall / 1e9, "served_GBps": tot / s_wall / 1e9,
+                      "batched_GBps": tot / b_wall / 1e9, "batched_counts": b_counts})
+        log(f"served load {load:g}: p99 plain {sweep[-1]['plain_p99_ms']:.2f} ms, served "
+            f"{sweep[-1]['served_p99_ms']:.2f} ms, batched {sweep[-1]['batched_p99_ms']:.2f} ms")
     return {
         "workload": f"{len(sizes)} MD-like streams, n log-uniform in [2^16, 2^24] (total "
                     f"{sum(sizes)}), {T} frames each, eb 1e-3 / 1e-4 x range alternating, "
                     f"requests C,D per frame in random stream order, Poisson arrivals at "
-                    f"{args.served_load:g} x plain capacity",
-        "requests": len(reqs), "workers": args.served_workers,
+                    f"the listed fractions of the plain form's capacity",
+        "requests": len(reqs), "workers": W, "batch_frames": BF,
+        "batch_particles": batch_particles,
         "plain_capacity_req_per_s": cap_rps,
         "plain_back_to_back_GBps": tot / plain_wall / 1e9,
         "served_back_to_back_GBps": tot / served_wall_b2b / 1e9,
-        "arrival_rate_req_per_s": rate,
-        "served_p50_ms": pct(s_lat, 50), "served_p99_ms": pct(s_lat, 99),
-        "plain_p50_ms": pct(p_lat, 50), "plain_p99_ms": pct(p_lat, 99),
-        "served_GBps": tot / s_wall / 1e9, "plain_GBps": tot / p_wall / 1e9,
+        "batched_back_to_back_GBps": tot / batched_wall_b2b / 1e9,
+        "batched_back_to_back_counts": b2b_counts,
+        "sweep": sweep,
         "record_sizes_equal_plain": True,
     }
 
@@ -519,7 +540,10 @@ def main():
     ap.add_argument("--served-streams", type=int, default=32)
     ap.add_argument("--served-frames", type=int, default=6)
     ap.add_argument("--served-workers", type=int, default=4)
-    ap.add_argument("--served-load", type=float, default=0.7)
+    ap.add_argument("--served-loads", type=lambda v: [float(x) for x in v.split(",")],
+                    default=[0.3, 0.6, 0.9, 1.5], help="arrival rates as fractions of plain capacity")
+    ap.add_argument("--served-batch", type=int, default=16,
+                    help="requests one merged launch set takes in the batched served leg")
     args = ap.parse_args()
     work = args.workloads.split(",")
 

@@ -284,8 +284,11 @@ lcp_status lcp_kernel_timer_read(lcp_plan_t plan, double* total_ms, uint64_t* la
  * LCP-T, decompress requests of LCP-T records -- share one set of launches:
  * one residual (or decode) launch and one coding (or reconstruction) launch
  * for up to batch_frames requests holding up to batch_particles particles in
- * all, on a batch scratch allocated per (fields, chunk size) when the first
- * such stream opens (counted against hbm_budget_bytes).  Records, frames and
+ * all, on batch scratch (one per worker) allocated for each (fields, chunk
+ * size) when the first such stream opens (counted against hbm_budget_bytes).
+ * A group forms when the first admissible request can be merged, a batch
+ * scratch of its kind is free and at least one further pending request can
+ * join it; otherwise that request runs alone as without merging.  Records, frames and
  * stream state are the same as without merging: a merged request whose LCP-T
  * record comes out larger than the stream's last LCP-S record, or whose record
  * turns out to be LCP-S, is put back at the front of the queue and runs
@@ -349,6 +352,12 @@ lcp_status lcp_server_submit(lcp_server_t server, const lcp_request* request, ui
 
 /* Block until the request is done and return its result (once per ticket). */
 lcp_status lcp_server_wait(lcp_server_t server, uint64_t ticket, lcp_result* result);
+
+/* hold != 0: workers start no further request (those running finish) until
+ * called again with hold == 0, so that a burst of submits is seen whole and
+ * merged as far as it can be.  Waiting on a held request blocks until the
+ * hold is lifted.  Errors: LCP_ERR_ARG (no server). */
+lcp_status lcp_server_hold(lcp_server_t server, int hold);
 
 /* Counters since creation: merged launch sets run, requests they finished,
  * requests they put back to run alone (any pointer may be NULL).

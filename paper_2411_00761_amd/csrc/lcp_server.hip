@@ -108,7 +108,7 @@ struct BatchSlot {
 
 struct lcp_server_s {
   lcp_server_params p{};
-  std::deque<BatchSlot> batches;  // stable addresses
+  std::deque<BatchSlot> batches;  // one per worker and key; stable addresses
   uint64_t merged_launches = 0, merged_requests = 0, requeued = 0;
   void* arena_mem = nullptr;
   Arena arena;
@@ -121,18 +121,25 @@ struct lcp_server_s {
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   bool stop = false;
+  bool hold = false;  // workers take no new request
   std::vector<std::thread> workers;
   lcp_status worker_error = LCP_OK;
 };
 
 namespace {
 
-BatchSlot* batch_for(lcp_server_s* S, const Ticket& t) {
+// A free batch scratch for the request's (fields, chunk size), if any.
+BatchSlot* free_batch_for(lcp_server_s* S, const Ticket& t) {
   if (t.solo) return nullptr;
   lcp_plan_s* P = S->streams[t.req.stream].plan;
   for (BatchSlot& b : S->batches)
-    if (b.F == plan_fields(P) && b.cl == plan_chunk_log2(P)) return &b;
+    if (!b.busy && b.F == plan_fields(P) && b.cl == plan_chunk_log2(P)) return &b;
   return nullptr;
+}
+
+bool same_key(lcp_server_s* S, const Ticket& t, const BatchSlot* b) {
+  lcp_plan_s* P = S->streams[t.req.stream].plan;
+  return !t.solo && b->F == plan_fields(P) && b->cl == plan_chunk_log2(P);
 }
 
 // Particles a request brings into a merged launch (at most).
@@ -140,8 +147,7 @@ uint64_t particles_of(const Ticket& t) {
   return t.req.kind == LCP_REQ_COMPRESS ? t.req.frame.n : t.req.dst.capacity;
 }
 
-bool mergeable(lcp_server_s* S, const Ticket& t, BatchSlot* b) {
-  if (!b || batch_for(S, t) != b) return false;
+bool mergeable(lcp_server_s* S, const Ticket& t) {
   if (t.req.kind == LCP_REQ_COMPRESS) return serve_t_eligible(S->streams[t.req.stream].plan, t.req.frame);
   // decompress: whether the record is temporal shows once its header is read;
   // a stream whose last record was temporal most likely sends another
@@ -149,13 +155,13 @@ bool mergeable(lcp_server_s* S, const Ticket& t, BatchSlot* b) {
 }
 
 // Next work (lock held), taken in arrival order among requests whose stream
-// is idle and has no earlier pending request.  The first such request that
-// can be merged leads a group, joined by the further ones of the same kind
-// and batch scratch, up to its frame and particle capacity; one that can be
-// merged while its batch scratch is in use waits for it.  The first request
-// that cannot be merged runs alone (single) on scratch from the arena; memory
-// is admitted strictly in order, so a large request is not starved by smaller
-// ones behind it.
+// is idle and has no earlier pending request.  When the first such request
+// can be merged and a batch scratch of its kind is free, it leads a group
+// joined by the further such requests of the same kind and batch key, up to
+// the frame and particle capacity; a group of two or more runs merged.
+// Otherwise that first request runs alone (single) on scratch from the arena;
+// memory is admitted strictly in order, so a large request is not starved by
+// smaller ones behind it.
 bool pick(lcp_server_s* S, std::vector<uint64_t>* group, BatchSlot** slot, uint64_t* single,
           size_t* off) {
   std::vector<char> blocked(S->streams.size(), 0);
@@ -163,42 +169,45 @@ bool pick(lcp_server_s* S, std::vector<uint64_t>* group, BatchSlot** slot, uint6
   *slot = nullptr;
   int kind = 0;
   uint64_t parts = 0;
+  auto first = S->pending.end();
   for (auto it = S->pending.begin(); it != S->pending.end(); ++it) {
     const Ticket& t = S->tickets[*it];
     const int sid = t.req.stream;
     if (blocked[sid]) continue;
     blocked[sid] = 1;
-    ServedStream& st = S->streams[sid];
-    if (st.busy) continue;
-    BatchSlot* b = batch_for(S, t);
-    const bool m = b && mergeable(S, t, b) && particles_of(t) <= serve_batch_particles(b->plan);
-    if (group->empty()) {
-      if (m && b->busy) continue;  // waits for its batch scratch
-      if (m) {
-        *slot = b;
-        kind = t.req.kind;
-        parts = particles_of(t);
-        group->push_back(*it);
-        continue;
-      }
-      if (!S->arena.alloc(st.scratch, off)) return false;
-      st.busy = true;
-      *single = *it;
-      S->pending.erase(it);
-      return true;
+    if (S->streams[sid].busy) continue;
+    if (first == S->pending.end()) {
+      first = it;
+      BatchSlot* b = free_batch_for(S, t);
+      if (!b || !mergeable(S, t) || particles_of(t) > serve_batch_particles(b->plan)) break;
+      *slot = b;
+      kind = t.req.kind;
+      parts = particles_of(t);
+      group->push_back(*it);
+      continue;
     }
     if ((int)group->size() >= serve_batch_frames((*slot)->plan)) break;
-    if (!m || b != *slot || t.req.kind != kind) continue;
-    if (parts + particles_of(t) > serve_batch_particles(b->plan)) continue;
+    if (t.req.kind != kind || !same_key(S, t, *slot) || !mergeable(S, t)) continue;
+    if (parts + particles_of(t) > serve_batch_particles((*slot)->plan)) continue;
     parts += particles_of(t);
     group->push_back(*it);
   }
-  if (group->empty()) return false;
-  for (uint64_t id : *group) {
-    S->streams[S->tickets[id].req.stream].busy = true;
-    S->pending.erase(std::find(S->pending.begin(), S->pending.end(), id));
+  if (group->size() >= 2) {
+    for (uint64_t id : *group) {
+      S->streams[S->tickets[id].req.stream].busy = true;
+      S->pending.erase(std::find(S->pending.begin(), S->pending.end(), id));
+    }
+    (*slot)->busy = true;
+    return true;
   }
-  (*slot)->busy = true;
+  group->clear();
+  *slot = nullptr;
+  if (first == S->pending.end()) return false;
+  ServedStream& st = S->streams[S->tickets[*first].req.stream];
+  if (!S->arena.alloc(st.scratch, off)) return false;
+  st.busy = true;
+  *single = *first;
+  S->pending.erase(first);
   return true;
 }
 
@@ -298,7 +307,7 @@ void worker_main(lcp_server_s* S) {
       std::unique_lock<std::mutex> lk(S->mu);
       if (init != LCP_OK) S->worker_error = init;
       S->cv_work.wait(lk, [&] {
-        return S->stop || (init == LCP_OK && pick(S, &group, &slot, &tk, &off));
+        return S->stop || (init == LCP_OK && !S->hold && pick(S, &group, &slot, &tk, &off));
       });
       if (S->stop && tk == 0 && group.empty()) break;
     }
@@ -425,7 +434,8 @@ lcp_status lcp_server_open_stream(lcp_server_t S, const lcp_params* params,
     bool have = false;
     for (const BatchSlot& b : S->batches)
       have |= b.F == plan_fields(plan) && b.cl == plan_chunk_log2(plan);
-    if (!have) {
+    // one batch scratch per worker for a new (fields, chunk size)
+    for (int w = 0; !have && w < S->p.workers; w++) {
       BatchSlot b;
       b.F = plan_fields(plan);
       b.cl = plan_chunk_log2(plan);
@@ -436,6 +446,11 @@ lcp_status lcp_server_open_stream(lcp_server_t S, const lcp_params* params,
         st = LCP_ERR_BUDGET;
       if (st) {
         if (b.plan) lcp_plan_destroy(b.plan);
+        while (!S->batches.empty() && S->batches.back().F == b.F && S->batches.back().cl == b.cl) {
+          S->state_used -= serve_batch_bytes(S->batches.back().plan);
+          lcp_plan_destroy(S->batches.back().plan);
+          S->batches.pop_back();
+        }
         S->state_used -= state;
         lcp_plan_destroy(plan);
         return st;
@@ -490,6 +505,16 @@ lcp_status lcp_server_wait(lcp_server_t S, uint64_t ticket, lcp_result* res) {
   if (!t.done) return S->worker_error;
   *res = t.res;
   S->tickets.erase(ticket);
+  return LCP_OK;
+}
+
+lcp_status lcp_server_hold(lcp_server_t S, int hold) {
+  if (!S) return LCP_ERR_ARG;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    S->hold = hold != 0;
+  }
+  S->cv_work.notify_all();
   return LCP_OK;
 }
 

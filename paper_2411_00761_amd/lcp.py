@@ -27,7 +27,8 @@ EXPORTED = ["lcp_plan", "lcp_plan_destroy", "lcp_plan_reset", "lcp_plan_block_lo
             "lcp_kernel_timer_read", "lcp_server_create", "lcp_server_destroy",
             "lcp_server_open_stream", "lcp_server_submit", "lcp_server_wait",
             "lcp_scratch_bytes", "lcp_compress_static", "lcp_plan_set_tuning",
-            "lcp_plan_get_tuning", "lcp_plan_autotune", "lcp_server_counts"]
+            "lcp_plan_get_tuning", "lcp_plan_autotune", "lcp_server_counts",
+            "lcp_server_hold"]
 REQ_COMPRESS, REQ_DECOMPRESS = 1, 2
 
 
@@ -172,6 +173,7 @@ def lib():
         L.lcp_server_wait.argtypes = [P, C.c_uint64, C.POINTER(lcp_result)]
         L.lcp_server_counts.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                         C.POINTER(C.c_uint64)]
+        L.lcp_server_hold.argtypes = [P, C.c_int]
         _lib = L
     return _lib
 
@@ -463,6 +465,10 @@ class Server:
         return {"status": r.status, "method": r.method, "bytes": r.bytes,
                 "t_submit_ns": r.t_submit_ns, "t_start_ns": r.t_start_ns, "t_end_ns": r.t_end_ns,
                 "group": r.group}
+
+    def hold(self, on: bool = True):
+        """lcp_server_hold: while on, workers start no further request."""
+        _check(lib().lcp_server_hold(self.h, int(on)), "lcp_server_hold")
 
     def counts(self) -> dict:
         """Launch sets run on batch scratch, requests they finished, requests put back."""

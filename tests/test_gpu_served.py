@@ -78,13 +78,19 @@ def serve(lcp, streams, workers, arena, batch_frames=0, batch_particles=0, count
     # interleave: frame t of every stream, compress then decompress
     sizes = [[None] * FRAMES for _ in streams]
     for t in range(FRAMES):
+        # each burst is queued whole before the workers look at it, so that
+        # merging (when enabled) sees every stream's request
+        srv.hold(True)
         ct = [srv.compress(ids[j], frames[j][t], outs[j][t]) for j in range(len(streams))]
+        srv.hold(False)
         for j, tk in enumerate(ct):
             r = srv.wait(tk)
             assert r["status"] == 0, (j, t, r)
             sizes[j][t] = r["bytes"]
+        srv.hold(True)
         tickets += [(j, t, srv.decompress(ids[j], outs[j][t], 0, sizes[j][t], decs[j][t]))
                     for j in range(len(streams))]
+        srv.hold(False)
     for j, t, tk in tickets:
         r = srv.wait(tk)
         assert r["status"] == 0 and r["bytes"] == streams[j][0].shape[1], (j, t, r)
@@ -172,7 +178,9 @@ def test_served_batched_forced_t_capacity(lcp):
         method = lcp.METHOD_AUTO if t == 0 else lcp.METHOD_T
         caps = [big, 64 if t == 2 else big]
         outs = [torch.zeros(c, dtype=torch.uint8, device="cuda") for c in caps]
+        srv.hold(True)
         tks = [srv.compress(sid, frames[t], outs[i], method=method) for i, sid in enumerate(sids)]
+        srv.hold(False)
         res = [srv.wait(tk) for tk in tks]
         for i in range(2):
             wout = torch.zeros(caps[i], dtype=torch.uint8, device="cuda")
