@@ -47,7 +47,7 @@ class OracleError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("eb_mode", C.c_int), ("eb", C.c_double), ("n_fields", C.c_int),
                 ("multi_frame", C.c_int), ("batch_size", C.c_int), ("block_log2", C.c_int),
-                ("chunk_log2", C.c_int)]
+                ("chunk_log2", C.c_int), ("anchor_scale", C.c_int)]
 
 
 class Grid(C.Structure):
@@ -62,7 +62,8 @@ class Info(C.Structure):
                 ("bn", C.c_uint32 * 3), ("m", C.c_float * MAX_F), ("eb_q", C.c_float * MAX_F),
                 ("coder", C.c_int * (MAX_F + 2)), ("param", C.c_int * (MAX_F + 2)),
                 ("used", C.c_uint32 * (MAX_F + 2)), ("arr_n", C.c_uint64 * (MAX_F + 2)),
-                ("arr_off", C.c_uint64 * (MAX_F + 2)), ("arr_bytes", C.c_uint64 * (MAX_F + 2))]
+                ("arr_off", C.c_uint64 * (MAX_F + 2)), ("arr_bytes", C.c_uint64 * (MAX_F + 2)),
+                ("scale", C.c_int)]
 
 
 _lib = None
@@ -94,7 +95,8 @@ def lib():
         L.lco_compress_s.argtypes = [P, C.c_int, C.c_uint64, P, C.c_int, C.c_int, C.c_uint64,
                                      P, C.c_uint64, C.POINTER(C.c_uint64), P, P]
         L.lco_compress_t.argtypes = [P, C.c_int, C.c_uint64, P, P, P, C.c_uint64, C.c_int,
-                                     C.c_uint64, P, C.c_uint64, C.POINTER(C.c_uint64), P]
+                                     C.c_int, C.c_uint64, P, C.c_uint64, C.POINTER(C.c_uint64),
+                                     P]
         L.lco_record_info.argtypes = [P, C.c_uint64, C.POINTER(Info)]
         L.lco_decompress.argtypes = [P, C.c_uint64, P, C.c_uint64, C.c_uint64, P, C.c_uint64,
                                      C.POINTER(C.c_uint64), P]
@@ -226,7 +228,7 @@ def compress_s(fields, grids, k, chunk_log2=10, seq=0):
     return out[: size.value].tobytes(), perm, q
 
 
-def compress_t(fields, grids, ref_perm, ref_q, ref_seq, chunk_log2=10, seq=1):
+def compress_t(fields, grids, ref_perm, ref_q, ref_seq, chunk_log2=10, seq=1, scale=1):
     arrs, ptrs = _fields(fields)
     F, n = len(arrs), len(arrs[0])
     cap = bound(F, n, chunk_log2)
@@ -235,7 +237,7 @@ def compress_t(fields, grids, ref_perm, ref_q, ref_seq, chunk_log2=10, seq=1):
     rp = np.ascontiguousarray(ref_perm, np.uint32)
     rq = np.ascontiguousarray(ref_q, np.int32)
     size = C.c_uint64()
-    _check(lib().lco_compress_t(ptrs, F, n, _grids(grids), _ptr(rp), _ptr(rq), ref_seq,
+    _check(lib().lco_compress_t(ptrs, F, n, _grids(grids), _ptr(rp), _ptr(rq), ref_seq, scale,
                                 chunk_log2, seq, _ptr(out), cap, C.byref(size), _ptr(q)),
            "compress_t")
     return out[: size.value].tobytes(), q
@@ -281,8 +283,9 @@ class Stream:
     """Alg. 1 multi-frame driver with LCP-FSM (compress and decompress sides)."""
 
     def __init__(self, eb_mode, eb, n_fields=3, multi_frame=1, batch_size=16, block_log2=4,
-                 chunk_log2=10, max_n=1 << 20):
-        self.p = Params(eb_mode, eb, n_fields, multi_frame, batch_size, block_log2, chunk_log2)
+                 chunk_log2=10, max_n=1 << 20, anchor_scale=0):
+        self.p = Params(eb_mode, eb, n_fields, multi_frame, batch_size, block_log2, chunk_log2,
+                        anchor_scale)
         self.F = n_fields
         self.max_n = max_n
         self.h = lib().lco_stream_create(C.byref(self.p), max_n)

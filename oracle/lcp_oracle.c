@@ -15,6 +15,8 @@
  *   LCP-FSM ................... Sec. 7.2 (S estimated by last S size; T tested with
  *                               a back-off S1X -> S2X -> S4X ...)
  *   anchor frames ............. Sec. 7.3, Alg. 1
+ *   anchor error-bound scale .. Sec. 7.4.2 (anchors at eb / 5 while frames are
+ *                               temporally correlated)
  *   block-size search ......... Sec. 7.4.1 (candidates 2^k, 0<=k<=16, on a sample)
  * The readings taken where the paper is silent (rounding margin, modular deltas,
  * escape classes, length limit, chunking, record layout, FSM details) are listed
@@ -527,8 +529,8 @@ uint64_t lco_bound(int F, uint64_t n, int chunk_log2) {
   return b;
 }
 
-static int write_record(int mode, int F, uint64_t n, uint64_t B, int k, int chunk_log2,
-                        const uint32_t* bn, uint64_t seq, uint64_t ref_seq,
+static int write_record(int mode, int scale, int F, uint64_t n, uint64_t B, int k,
+                        int chunk_log2, const uint32_t* bn, uint64_t seq, uint64_t ref_seq,
                         const lco_grid* grids, const arr_in* arrs, int A, uint8_t* out,
                         uint64_t cap, uint64_t* size) {
   uint64_t hdr = HDR_BYTES + 8 * (uint64_t)F + DIR_BYTES * (uint64_t)A;
@@ -553,7 +555,7 @@ static int write_record(int mode, int F, uint64_t n, uint64_t B, int k, int chun
   put_u8(out + 8, (unsigned)k);
   put_u8(out + 9, (unsigned)chunk_log2);
   put_u8(out + 10, (unsigned)A);
-  put_u8(out + 11, 0);
+  put_u8(out + 11, scale > 1 ? (unsigned)scale : 0u); /* T residual step; 0 means 1 */
   put_u32(out + 12, (uint32_t)hdr);
   put_u64(out + 16, n);
   put_u64(out + 24, B);
@@ -693,7 +695,7 @@ int lco_compress_s(const float* const* x, int F, uint64_t n, const lco_grid* gri
     arrs[2 + f].v = v_sup[f];
     arrs[2 + f].n = n;
   }
-  st = write_record(0, F, n, B, k, chunk_log2, bn, seq, UINT64_MAX, grids, arrs, F + 2, out,
+  st = write_record(0, 1, F, n, B, k, chunk_log2, bn, seq, UINT64_MAX, grids, arrs, F + 2, out,
                     cap, size);
   if (st == LCO_OK && perm_out)
     for (uint64_t s = 0; s < n; s++) perm_out[s] = ki[s].idx;
@@ -717,9 +719,10 @@ int lco_compress_s(const float* const* x, int F, uint64_t n, const lco_grid* gri
 /* ------------------------------------------------------------------ */
 int lco_compress_t(const float* const* x, int F, uint64_t n, const lco_grid* grids,
                    const uint32_t* ref_perm, const int32_t* ref_q, uint64_t ref_seq,
-                   int chunk_log2, uint64_t seq, uint8_t* out, uint64_t cap,
+                   int scale, int chunk_log2, uint64_t seq, uint8_t* out, uint64_t cap,
                    uint64_t* size, int32_t* q_slot) {
   if (F < 3 || F > LCO_MAX_F || n == 0 || n > ((uint64_t)1 << 31)) return LCO_ERR_ARG;
+  if (scale < 1 || scale > 15 || scale % 2 == 0) return LCO_ERR_ARG;
   if (!ref_perm || !ref_q) return LCO_ERR_NO_REFERENCE;
   float lo[LCO_MAX_F], hi[LCO_MAX_F];
   int st = lco_extent(x, F, n, lo, hi);
@@ -732,20 +735,38 @@ int lco_compress_t(const float* const* x, int F, uint64_t n, const lco_grid* gri
     if (lco_quant(lo[f], &grids[f]) < -Q_LIMIT) return LCO_ERR_RANGE;
     if (lco_quant(hi[f], &grids[f]) >= Q_LIMIT) return LCO_ERR_RANGE;
   }
+  /* Sec. 7.1: quantise the frame, subtract the reference.  With an anchor grid
+   * made at eb / s (Sec. 7.4.2) the frame is coded at eb on that finer grid: its
+   * code moves from the reference's by a multiple of s, the one nearest to the
+   * frame's own code (within (s - 1) / 2 of it, so the reconstruction is within
+   * s bins' half width, i.e. eb).  The residual is that multiple divided by s. */
+  const int64_t h = (scale - 1) / 2;
   uint64_t* v[LCO_MAX_F];
   arr_in arrs[LCO_MAX_F];
   for (int f = 0; f < F; f++) {
     v[f] = (uint64_t*)malloc(sizeof(uint64_t) * n);
-    for (uint64_t s = 0; s < n; s++) {
-      int64_t q = lco_quant(x[f][ref_perm[s]], &grids[f]);
-      v[f][s] = zigzag(q - (int64_t)ref_q[(uint64_t)f * n + s]);
-      if (q_slot) q_slot[(uint64_t)f * n + s] = (int32_t)q;
-    }
     arrs[f].v = v[f];
     arrs[f].n = n;
   }
-  st = write_record(1, F, n, 0, 0, chunk_log2, NULL, seq, ref_seq, grids, arrs, F, out, cap,
-                    size);
+  for (int f = 0; f < F && st == LCO_OK; f++) {
+    for (uint64_t s = 0; s < n; s++) {
+      int64_t q = lco_quant(x[f][ref_perm[s]], &grids[f]);
+      int64_t ref = (int64_t)ref_q[(uint64_t)f * n + s];
+      int64_t num = q - ref + h;
+      /* floor division, exact for negative numerators too */
+      int64_t r = num >= 0 ? num / scale : -((-num + scale - 1) / scale);
+      int64_t qn = ref + (int64_t)scale * r;
+      if (qn < -Q_LIMIT || qn >= Q_LIMIT) {
+        st = LCO_ERR_RANGE;
+        break;
+      }
+      v[f][s] = zigzag(r);
+      if (q_slot) q_slot[(uint64_t)f * n + s] = (int32_t)qn;
+    }
+  }
+  if (st == LCO_OK)
+    st = write_record(1, scale, F, n, 0, 0, chunk_log2, NULL, seq, ref_seq, grids, arrs, F, out,
+                      cap, size);
   for (int f = 0; f < F; f++) free(v[f]);
   return st;
 }
@@ -762,6 +783,9 @@ int lco_record_info(const uint8_t* rec, uint64_t size, lco_info* info) {
   info->k = rec[8];
   info->chunk_log2 = rec[9];
   info->n_arrays = rec[10];
+  info->scale = rec[11] ? rec[11] : 1;
+  if ((info->mode == 0 && rec[11] != 0) || info->scale > 15 || info->scale % 2 == 0)
+    return LCO_ERR_CORRUPT;
   if (info->mode > 1 || info->F < 3 || info->F > LCO_MAX_F || info->k > 16 ||
       info->chunk_log2 < 5 || info->chunk_log2 > 16)
     return LCO_ERR_CORRUPT;
@@ -866,7 +890,10 @@ int lco_decompress(const uint8_t* rec, uint64_t size, const int32_t* ref_q,
     if (!ref_q || ref_seq != I.ref_seq || ref_n != n) st = LCO_ERR_NO_REFERENCE;
     for (int f = 0; f < I.F && st == LCO_OK; f++)
       for (uint64_t t = 0; t < n; t++) {
-        int64_t qq = (int64_t)ref_q[(uint64_t)f * n + t] + unzigzag(v[f][t]);
+        /* residuals of a valid record are below 2^26; a larger one is corrupt
+         * (and would overflow the scaled sum) */
+        int64_t d = v[f][t] < ((uint64_t)1 << 40) ? unzigzag(v[f][t]) : ((int64_t)1 << 40);
+        int64_t qq = (int64_t)ref_q[(uint64_t)f * n + t] + (int64_t)I.scale * d;
         if (qq < -Q_LIMIT || qq >= Q_LIMIT) {
           st = LCO_ERR_CORRUPT;
           break;
@@ -890,6 +917,7 @@ int lco_decompress(const uint8_t* rec, uint64_t size, const int32_t* ref_q,
 /* ------------------------------------------------------------------ */
 typedef struct {
   int valid;
+  int scale; /* the grid's step relative to the stream's bound: 1, or an anchor's scale */
   uint64_t seq, n;
   lco_grid grid[LCO_MAX_F];
   uint32_t* perm;
@@ -908,6 +936,8 @@ struct lco_stream {
   int interval;  /* S state: compare once every `interval` frames */
   int countdown; /* S frames left before the next comparison */
   uint64_t last_s;
+  /* frames coded since the last anchor, and how many of them by LCP-T */
+  uint64_t n_since_anchor, t_since_anchor;
   /* decompress side */
   uint64_t dseq;
   ref_t dprev, danchor;
@@ -924,6 +954,7 @@ static void ref_free(ref_t* r) {
 }
 static void ref_copy(ref_t* dst, const ref_t* src, int F) {
   dst->valid = src->valid;
+  dst->scale = src->scale;
   dst->seq = src->seq;
   dst->n = src->n;
   memcpy(dst->grid, src->grid, sizeof(src->grid));
@@ -936,7 +967,8 @@ static void ref_copy(ref_t* dst, const ref_t* src, int F) {
 lco_stream* lco_stream_create(const lco_params* p, uint64_t max_n) {
   if (!p || p->n_fields < 3 || p->n_fields > LCO_MAX_F || p->block_log2 < 0 ||
       p->block_log2 > 16 || p->chunk_log2 < 5 || p->chunk_log2 > 16 || p->batch_size < 0 ||
-      max_n == 0)
+      max_n == 0 || p->anchor_scale < 0 || p->anchor_scale > 15 ||
+      (p->anchor_scale > 1 && p->anchor_scale % 2 == 0))
     return NULL;
   lco_stream* s = (lco_stream*)calloc(1, sizeof(lco_stream));
   s->p = *p;
@@ -1046,14 +1078,23 @@ int lco_stream_compress(lco_stream* s, const float* const* x, uint64_t n, int me
   if (decision != LCO_DECIDE_S) {
     bt = (uint8_t*)malloc(bound);
     q_t = (int32_t*)malloc(sizeof(int32_t) * n * F);
-    int st2 = lco_compress_t(x, F, n, ref->grid, ref->perm, ref->q, ref->seq,
+    int st2 = lco_compress_t(x, F, n, ref->grid, ref->perm, ref->q, ref->seq, ref->scale,
                              s->p.chunk_log2, s->seq, bt, bound, &size_tt, q_t);
     if (st2 == LCO_OK) have_t = 1;
     else if (st2 != LCO_ERR_RANGE || method == LCO_METHOD_T) st = st2; /* RANGE: T infeasible */
   }
   int need_s = decision != LCO_DECIDE_T || !have_t ||
                (method == LCO_METHOD_AUTO && size_tt > s->last_s);
-  for (int f = 0; f < F && st == LCO_OK && need_s; f++) st = lco_make_grid(lo[f], hi[f], eb_f[f], &sg[f]);
+  /* Sec. 7.4.2: a frame that would become an anchor (first in its batch, coded
+   * by S) is coded at eb / s while the stream's frames are temporally
+   * correlated, read as: no frame coded since the last anchor yet (the stream's
+   * start), or at least half of those frames coded by LCP-T. */
+  int s_scale = 1;
+  if (s->p.multi_frame && s->p.anchor_scale > 1 && first_in_batch(&s->p, s->seq) &&
+      (s->n_since_anchor == 0 || 2 * s->t_since_anchor >= s->n_since_anchor))
+    s_scale = s->p.anchor_scale;
+  for (int f = 0; f < F && st == LCO_OK && need_s; f++)
+    st = lco_make_grid(lo[f], hi[f], eb_f[f] / (double)s_scale, &sg[f]);
   if (st == LCO_OK && need_s) {
     bs = (uint8_t*)malloc(bound);
     perm_s = (uint32_t*)malloc(sizeof(uint32_t) * n);
@@ -1072,11 +1113,14 @@ int lco_stream_compress(lco_stream* s, const float* const* x, uint64_t n, int me
     memcpy(out, chose_t ? bt : bs, chosen);
     *size = chosen;
     if (method_used) *method_used = chose_t ? LCO_METHOD_T : LCO_METHOD_S;
-    if (have_s) s->last_s = size_s;
+    /* the estimate of S is an S record at the stream's bound; an anchor coded
+     * at eb / s stands in only until there is one */
+    if (have_s && (s_scale == 1 || s->last_s == 0)) s->last_s = size_s;
     if (s->p.multi_frame && method == LCO_METHOD_AUTO) fsm_update(s, decision, ref != NULL, chose_t);
     /* Alg. 1 bookkeeping: the previous frame; anchors are first-in-batch S frames */
     if (!chose_t) {
       s->prev.valid = 1;
+      s->prev.scale = s_scale;
       s->prev.seq = s->seq;
       s->prev.n = n;
       memcpy(s->prev.grid, sg, sizeof(sg));
@@ -1089,12 +1133,20 @@ int lco_stream_compress(lco_stream* s, const float* const* x, uint64_t n, int me
         memcpy(s->prev.grid, ref->grid, sizeof(ref->grid));
         memcpy(s->prev.perm, ref->perm, sizeof(uint32_t) * n);
       }
+      s->prev.scale = ref->scale;
       s->prev.valid = 1;
       s->prev.seq = s->seq;
       s->prev.n = n;
       memcpy(s->prev.q, q_t, sizeof(int32_t) * n * F);
     }
     if (perm_out) memcpy(perm_out, s->prev.perm, sizeof(uint32_t) * n);
+    if (!chose_t && first_in_batch(&s->p, s->seq)) {
+      s->n_since_anchor = 0;
+      s->t_since_anchor = 0;
+    } else {
+      s->n_since_anchor++;
+      s->t_since_anchor += chose_t ? 1 : 0;
+    }
     if (s->p.multi_frame && !s->have_eb) {
       memcpy(s->eb_f, eb_f, sizeof(eb_f));
       s->have_eb = 1;

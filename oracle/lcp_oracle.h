@@ -48,6 +48,8 @@ typedef struct {
   int batch_size;   /* Alg. 1 batch length; 0 = one unbounded batch */
   int block_log2;   /* k in [0,16]; p = 2^k quantisation bins per block side */
   int chunk_log2;   /* Huffman chunk = 2^chunk_log2 symbols, in [5,16] */
+  int anchor_scale; /* 0 or 1: off; odd 3..15: an anchor frame is coded at eb / anchor_scale
+                       while the stream's temporal correlation is high (Sec. 7.4.2) */
 } lco_params;
 
 /* Quantisation grid of one field (Eq. 5 with the FP32 rounding margin). */
@@ -70,6 +72,7 @@ typedef struct {
   int param[LCO_MAX_F + 2];   /* width w, or longest code length */
   uint32_t used[LCO_MAX_F + 2];
   uint64_t arr_n[LCO_MAX_F + 2], arr_off[LCO_MAX_F + 2], arr_bytes[LCO_MAX_F + 2];
+  int scale;           /* T records: code step of the residuals (1, or an anchor's scale) */
 } lco_info;
 
 /* ---- step-level entry points (pins and parity at every step) ---- */
@@ -96,10 +99,12 @@ int lco_decode_array(const uint8_t* data, uint64_t nbytes, uint64_t n, int coder
 int lco_compress_s(const float* const* x, int F, uint64_t n, const lco_grid* grids,
                    int k, int chunk_log2, uint64_t seq, uint8_t* out, uint64_t cap,
                    uint64_t* size, uint32_t* perm, int32_t* q_slot);
-/* LCP-T against a reference (grids, slot permutation, slot-order codes). */
+/* LCP-T against a reference (grids, slot permutation, slot-order codes).  scale
+ * is 1, or the anchor scale s when the reference grid is an anchor's grid made at
+ * eb / s: the frame's codes then move in steps of s on that grid (Sec. 7.4.2). */
 int lco_compress_t(const float* const* x, int F, uint64_t n, const lco_grid* grids,
                    const uint32_t* ref_perm, const int32_t* ref_q, uint64_t ref_seq,
-                   int chunk_log2, uint64_t seq, uint8_t* out, uint64_t cap,
+                   int scale, int chunk_log2, uint64_t seq, uint8_t* out, uint64_t cap,
                    uint64_t* size, int32_t* q_slot);
 int lco_record_info(const uint8_t* rec, uint64_t size, lco_info* info);
 /* Decode a record.  T records need ref_q ([F][n] slot order) of the frame whose

@@ -118,8 +118,10 @@ def parse(rec: bytes, arrays: bool = True) -> dict:
             arrays.append(decode_array(rec[aoff:aoff + anb], an, coder, param, used, cl))
         off += anb
     assert off == total
+    # byte 11: the step of a temporal record's residuals (0 meaning 1); zero in S records
+    assert (flags == 0) if mode == 0 else (flags == 0 or flags % 2 == 1)
     return dict(mode=mode, F=F, k=k, chunk_log2=cl, n=n, B=B, bn=bn, seq=seq, ref_seq=ref_seq,
-                grids=grids, dirs=dirs, arrays=arrays)
+                grids=grids, dirs=dirs, arrays=arrays, scale=flags if flags else 1)
 
 
 def s_codes(rec: bytes):
