@@ -85,6 +85,13 @@ typedef struct {
                                    (0 = max_particles) */
   int max_batch_frames;         /* single-frame plans: most frames in one batch, at most
                                    1024 (0 = 64) */
+  int anchor_scale;             /* multi-frame plans (Sec. 7.4.2): 0 or 1 = off; an odd
+                                   s in 3..15 codes an anchor frame (first in its batch,
+                                   LCP-S) at eb / s while the stream is temporally
+                                   correlated -- at its start, or when at least half of
+                                   the frames since the last anchor were LCP-T; the
+                                   LCP-T frames chained to it keep its finer grid and
+                                   move in steps of s (the paper uses s = 5) */
 } lcp_params;
 
 typedef struct lcp_plan_s* lcp_plan_t;
@@ -253,11 +260,16 @@ lcp_status lcp_plan_autotune(lcp_plan_t plan, uint64_t n_frames, const lcp_frame
                              lcp_tuning* chosen, double* best_ms, double* default_ms);
 
 /* Kernel timing for roofline measurement: while a name is set, one launch in
- * sixteen of the kernel with that name (the first, the 17th, ...) carries HIP
- * events on its own dispatch; the accumulated time (ms), count and algorithmic
- * bytes of the timed launches are read back with lcp_kernel_timer_read.
- * Sampling keeps the events' cost on the stream (a few microseconds around each
- * timed launch) out of the other launches.  Pass NULL to stop. */
+ * sixteen of the kernel with that name (the first, the 17th, ...; "name/N"
+ * times one in N, N in 1..1024) carries HIP events on its own dispatch; the
+ * accumulated time (ms), count and algorithmic bytes of the timed launches are
+ * read back with lcp_kernel_timer_read.  Sampling keeps the events' cost on the
+ * stream (a few microseconds around each timed launch) out of the other
+ * launches.  Names: "t_resid" (one temporal frame, or frames of several
+ * streams), "t_resid_run" (a run of temporal frames of one stream), "t_recon",
+ * "quant_key", "radix_scatter", "slot_syms", "s_recon", "extent", "hist",
+ * "huff_build", "pack_huff", "emit", "layout", "decode_huff", "decode_fixed".
+ * Pass NULL to stop. */
 lcp_status lcp_kernel_timer_set(lcp_plan_t plan, const char* kernel_name);
 lcp_status lcp_kernel_timer_read(lcp_plan_t plan, double* total_ms, uint64_t* launches,
                                  uint64_t* bytes);

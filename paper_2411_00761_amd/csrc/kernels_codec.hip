@@ -895,7 +895,9 @@ __device__ inline void write_header(const RecHdr& h, uint64_t B, uint64_t size, 
   const uint64_t hdr = (uint64_t)kHdrBytes + 8ull * h.F + (uint64_t)kDirBytes * h.A;
   put32(out, 0, kMagic);
   put32(out, 4, (uint32_t)kVersion | ((uint32_t)h.mode << 16) | ((uint32_t)h.F << 24));
-  put32(out, 8, (uint32_t)h.k | ((uint32_t)h.chunk_log2 << 8) | ((uint32_t)h.A << 16));
+  // byte 11: a temporal record's residual step (Sec. 7.4.2), 0 standing for 1
+  const uint32_t step = h.scale > 1 ? (uint32_t)h.scale : 0u;
+  put32(out, 8, (uint32_t)h.k | ((uint32_t)h.chunk_log2 << 8) | ((uint32_t)h.A << 16) | (step << 24));
   put32(out, 12, (uint32_t)hdr);
   put64(out, 16, h.n);
   put64(out, 24, B);

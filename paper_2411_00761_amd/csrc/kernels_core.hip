@@ -250,6 +250,28 @@ __device__ inline uint32_t t_code(float xv, const GridDev& g, int f, uint32_t* b
   return 0;
 }
 
+// Sec. 7.1 with the anchor scale of Sec. 7.4.2: a temporal frame's code on its
+// reference grid moves from the reference's code by a multiple of the grid's
+// step s, the multiple nearest the frame's own code q (within (s - 1) / 2 of
+// it, s odd); the residual is that multiple over s.  With s = 1 the code is q
+// itself.  A code outside the code range flags the frame.
+__device__ inline int64_t t_step(int64_t q, int64_t ref, int32_t s, uint32_t* bad, int64_t* qn) {
+  if (s == 1) {
+    *qn = q;
+    return q - ref;
+  }
+  // |q|, |ref| < 2^23 here, so the difference fits 32 bits
+  const int32_t num = (int32_t)(q - ref) + (s - 1) / 2;
+  const int32_t r = num >= 0 ? num / s : -((-num + s - 1) / s);
+  int64_t c = ref + (int64_t)s * r;
+  if (c < -(int64_t)kQLimit || c >= (int64_t)kQLimit) {
+    *bad |= kErrRange;
+    c = 0;
+  }
+  *qn = c;
+  return r;
+}
+
 // Per-wave private bins of the fused residual histogram (symbols below this).
 constexpr int kResPriv = 256;
 
@@ -297,10 +319,10 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
         int32_t qv[4];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
-          int64_t q;
+          int64_t q, qn;
           t_code(xv[j], g, f, &bad, &q);
-          rv[j] = (uint32_t)zigzag64(q - (int64_t)qrv[j]);
-          qv[j] = (int32_t)q;
+          rv[j] = (uint32_t)zigzag64(t_step(q, qrv[j], g.scale, &bad, &qn));
+          qv[j] = (int32_t)qn;
           rmax[f] = max(rmax[f], rv[j]);
         }
         if (v8) {
@@ -323,9 +345,10 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
     for (uint64_t s = gid; s < n; s += stride) {
       uint32_t i = perm_ref[s];
       for (int f = 0; f < F; f++) {
-        int64_t q;
-        t_code(x.p[f][i], g, f, &bad, &q);
-        const uint32_t r = (uint32_t)zigzag64(q - (int64_t)q_ref[(uint64_t)f * n + s]);
+        int64_t q0, q;
+        t_code(x.p[f][i], g, f, &bad, &q0);
+        const uint32_t r =
+            (uint32_t)zigzag64(t_step(q0, q_ref[(uint64_t)f * n + s], g.scale, &bad, &q));
         if (v8) {
           v8[(uint64_t)f * n + s] = (uint8_t)min(r, 255u);
           if (r >= 255u) v_res[(uint64_t)f * n + s] = r;
@@ -452,9 +475,9 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
         uint32_t rv[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-          int64_t qn = 0;
-          if (mine) t_code(xv[u], g, f, &bad, &qn);
-          rv[u] = (uint32_t)zigzag64(qn - (int64_t)q[f][u]);
+          int64_t qc = 0, qn = 0;
+          if (mine) t_code(xv[u], g, f, &bad, &qc);
+          rv[u] = (uint32_t)zigzag64(t_step(qc, q[f][u], g.scale, &bad, &qn));
           q[f][u] = (int32_t)qn;
           if (mine) rmax = max(rmax, rv[u]);
         }
@@ -475,9 +498,9 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
       } else {
         uint32_t r = 0;
         if (mine) {
-          int64_t qn;
-          t_code(x[idx[0]], g, f, &bad, &qn);
-          r = (uint32_t)zigzag64(qn - (int64_t)q[f][0]);
+          int64_t qc, qn;
+          t_code(x[idx[0]], g, f, &bad, &qc);
+          r = (uint32_t)zigzag64(t_step(qc, q[f][0], g.scale, &bad, &qn));
           q[f][0] = (int32_t)qn;
           out8[gid] = (uint8_t)min(r, 255u);
           if (r >= 255u) oesc[gid] = r;
@@ -561,9 +584,10 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_multi(const TFrameDev* T, 
     if (mine) {
       const uint64_t s0 = fr.vec ? 4 * item : item;
       for (int u = 0; u < cnt; u++) {
-        int64_t q;
-        t_code(fr.x[f][idx[u]], fr.g, f, &bad, &q);
-        rv[u] = (uint32_t)zigzag64(q - (int64_t)fr.q_ref[(uint64_t)f * n + s0 + u]);
+        int64_t qc, q;
+        t_code(fr.x[f][idx[u]], fr.g, f, &bad, &qc);
+        rv[u] = (uint32_t)zigzag64(
+            t_step(qc, fr.q_ref[(uint64_t)f * n + s0 + u], fr.g.scale, &bad, &q));
         fr.q_new[(uint64_t)f * n + s0 + u] = (int32_t)q;
         fr.v8[(uint64_t)f * n + s0 + u] = (uint8_t)min(rv[u], 255u);
         if (rv[u] >= 255u) fr.esc[(uint64_t)f * n + s0 + u] = rv[u];
@@ -617,7 +641,7 @@ __global__ __launch_bounds__(kThreads) void k_t_recon_multi(const TReconDev* T, 
       if (s >= n) break;
       int32_t rr = fr.r8[(uint64_t)f * n + s];
       if (rr == -128) rr = reinterpret_cast<const int32_t*>(fr.out[f])[s];
-      int64_t q = (int64_t)fr.q_ref[(uint64_t)f * n + s] + rr;
+      int64_t q = (int64_t)fr.q_ref[(uint64_t)f * n + s] + (int64_t)fr.scale * rr;
       if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
         bad = 1;
         q = 0;
@@ -630,20 +654,28 @@ __global__ __launch_bounds__(kThreads) void k_t_recon_multi(const TReconDev* T, 
 }
 
 // The codes a temporal frame leaves as the next frame's reference: the frame's
-// Eq. 5 codes on its reference grid, in the reference's slot order.  They
-// depend on the frame, the grid and the slot order only (not on the
-// reference's codes), so they can be rebuilt when their slot was reused.
-__global__ __launch_bounds__(kThreads) void k_t_codes(FieldPtrs x, int F, uint64_t n, GridDev g,
-                                                      const uint32_t* perm_ref, int32_t* q_new,
+// Eq. 5 codes on its reference grid, in the reference's slot order, moved in
+// steps of the grid's scale from the reference's codes.  With step 1 they
+// depend on the last frame alone; with a larger step the chain of J frames is
+// followed from the codes q_ref of their first reference.  Either way they can
+// be rebuilt when their slot was reused.
+__global__ __launch_bounds__(kThreads) void k_t_codes(RunFrames fr, int J, int F, uint64_t n,
+                                                      GridDev g, const uint32_t* perm_ref,
+                                                      const int32_t* q_ref, int32_t* q_new,
                                                       uint32_t* err) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   uint32_t bad = 0;
+  const int j0 = g.scale == 1 ? J - 1 : 0;
   for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
     const uint32_t i = perm_ref[s];
     for (int f = 0; f < F; f++) {
-      int64_t q;
-      t_code(x.p[f][i], g, f, &bad, &q);
-      q_new[(uint64_t)f * n + s] = (int32_t)q;
+      int64_t c = g.scale == 1 ? 0 : q_ref[(uint64_t)f * n + s];
+      for (int j = j0; j < J; j++) {
+        int64_t q;
+        t_code(fr.x[j][f][i], g, f, &bad, &q);
+        t_step(q, c, g.scale, &bad, &c);
+      }
+      q_new[(uint64_t)f * n + s] = (int32_t)c;
     }
   }
   if (bad) atomicOr(err, bad);
@@ -1127,8 +1159,9 @@ __global__ __launch_bounds__(kThreads) void k_t_recon(const int32_t* q_ref, int 
       for (int f = 0; f < F; f++) {
         const int4 r = reinterpret_cast<const int4*>(out.p[f])[s4];
         const int4 qr = reinterpret_cast<const int4*>(q_ref + (uint64_t)f * n)[s4];
-        int64_t q[4] = {(int64_t)qr.x + r.x, (int64_t)qr.y + r.y, (int64_t)qr.z + r.z,
-                        (int64_t)qr.w + r.w};
+        const int64_t sc = g.scale;
+        int64_t q[4] = {(int64_t)qr.x + sc * r.x, (int64_t)qr.y + sc * r.y,
+                        (int64_t)qr.z + sc * r.z, (int64_t)qr.w + sc * r.w};
         float o[4];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
@@ -1148,7 +1181,7 @@ __global__ __launch_bounds__(kThreads) void k_t_recon(const int32_t* q_ref, int 
     for (uint64_t s = gid; s < n; s += stride) {
       for (int f = 0; f < F; f++) {
         const int32_t r = reinterpret_cast<const int32_t*>(out.p[f])[s];
-        int64_t q = (int64_t)q_ref[(uint64_t)f * n + s] + (int64_t)r;
+        int64_t q = (int64_t)q_ref[(uint64_t)f * n + s] + (int64_t)g.scale * r;
         if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
           bad = 1;
           q = 0;
@@ -1185,7 +1218,7 @@ __global__ __launch_bounds__(kThreads) void k_t_recon_chain(const int32_t* q_ref
           float v[4];
 #pragma unroll
           for (int u = 0; u < 4; u++) {
-            q[u] += rr[u];
+            q[u] += (int64_t)g.scale * rr[u];
             if (q[u] < -(int64_t)kQLimit || q[u] >= (int64_t)kQLimit) {
               bad = 1;
               q[u] = 0;
@@ -1265,7 +1298,7 @@ __global__ __launch_bounds__(kThreads) void k_t_recon_chain(const int32_t* q_ref
           } else {
             r = reinterpret_cast<const int32_t*>(out.p[j][f])[s];
           }
-          q += r;
+          q += (int64_t)g.scale * r;
           if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
             bad = 1;
             q = 0;
@@ -1510,9 +1543,12 @@ void launch_t_resid_run(const RunFrames& fr, int J, int F, uint64_t n, const Gri
   int vec = (n % 4 == 0) && al16(perm) && al16(q_ref) && (!q_last || al16(q_last)) &&
             (astride % 16 == 0) && al16(v8);
   const uint64_t items = vec ? n / 4 : n;
-  // algorithmic bytes of the run: the J frames read and their residual bytes
-  // written; the permutation and the first reference codes read, the last
-  // codes written, once for the run
+  // algorithmic bytes: the per-frame figure of LCP-T compression (a frame, its
+  // reference codes and the permutation read, its codes written: 4 + 12F per
+  // particle) for each of the J frames.  The kernel itself moves less -- J
+  // frames read and their residual bytes written, the permutation and the first
+  // reference codes read and the last codes written once -- since the codes
+  // stay in registers from frame to frame
   auto* kernel = k_t_resid_run<3>;
   switch (F) {
     case 4: kernel = k_t_resid_run<4>; break;
@@ -1522,7 +1558,7 @@ void launch_t_resid_run(const RunFrames& fr, int J, int F, uint64_t n, const Gri
     case 8: kernel = k_t_resid_run<8>; break;
     default: break;
   }
-  launch_timed("t_resid", n * ((uint64_t)J * 5 * F + 4 + 8ull * F), kernel,
+  launch_timed("t_resid_run", n * (uint64_t)J * (4 + 12ull * F), kernel,
                grid_for(items, kThreads, 1u << 24), kThreads,
                (size_t)J * F * kRunPriv * 4, s, fr, J, n, g, perm, q_ref,
                q_last, v8, vesc, astride, a0, hist_part, hist_max, copies, zero_words, err,
@@ -1549,10 +1585,11 @@ void launch_t_recon_multi(const TReconDev* frames, const uint32_t* pre, uint32_t
   launch_timed("t_recon", bytes, k_t_recon_multi, blocks, kThreads, 0, s, frames, pre, R, F, err);
 }
 
-void launch_t_codes(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
-                    const uint32_t* perm_ref, int32_t* q_new, uint32_t* err, hipStream_t s) {
-  k_t_codes<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(x, F, n, g, perm_ref, q_new,
-                                                                      err);
+void launch_t_codes(const RunFrames& fr, int J, int F, uint64_t n, const GridDev& g,
+                    const uint32_t* perm_ref, const int32_t* q_ref, int32_t* q_new,
+                    uint32_t* err, hipStream_t s) {
+  k_t_codes<<<grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s>>>(fr, J, F, n, g, perm_ref,
+                                                                      q_ref, q_new, err);
 }
 
 void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, uint64_t B,

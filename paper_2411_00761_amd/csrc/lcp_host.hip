@@ -29,9 +29,10 @@ namespace {
 // host round trip per kTRun frames.
 constexpr int kTRun = 32;
 constexpr int kTRunStart = 8;
-// The kernel timer brackets one launch in kTimerStride of the named kernel:
-// each timed launch costs the stream some microseconds on either side (the
-// events' own packets), which a sampled average keeps out of the rest.
+// The kernel timer brackets one launch in kTimerStride (or the stride the
+// name asks for) of the named kernel: each timed launch costs the stream some
+// microseconds on either side (the events' own packets), which a sampled
+// average keeps out of the rest.
 constexpr uint64_t kTimerStride = 16;
 // Temporal frames whose residuals one decode launch keeps as bytes.
 constexpr int kDecSlots = kChainMax;
@@ -98,6 +99,7 @@ struct DevBuf {
 
 struct RefState {
   bool valid = false;
+  int scale = 1;  // the grid's step against the stream's bound: 1, or an anchor's scale
   uint64_t seq = 0, n = 0;
   HostGrid grid[kMaxF];
   int q = -1;     // index into the q pool
@@ -215,6 +217,9 @@ struct lcp_plan_s {
   uint64_t last_s = 0;
   bool have_last_s = false;
   bool dec_last_t = false;  // the last record decoded was LCP-T
+  // frames coded since the last anchor, and how many of them by LCP-T (the
+  // temporal-correlation gate of the anchor scale, Sec. 7.4.2)
+  uint64_t n_since_anchor = 0, t_since_anchor = 0;
 
   // launch shape of the batch encode kernels (tuned, or the defaults) and the
   // graphs captured for batches of LCP-S frames, keyed by their launch shape
@@ -228,6 +233,7 @@ struct lcp_plan_s {
 
   // kernel timer
   char timer_name[64] = {0};
+  uint64_t timer_every = kTimerStride;
   std::vector<hipEvent_t> ev_free;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_pending;
   std::vector<uint64_t> ev_bytes;
@@ -351,6 +357,7 @@ uint64_t bound_bytes(int F, uint64_t n) {
 GridDev to_dev(const HostGrid* g, int F) {
   GridDev d;
   memset(&d, 0, sizeof(d));
+  d.scale = 1;
   for (int f = 0; f < F; f++) {
     d.m[f] = g[f].m;
     d.eb_q[f] = g[f].eb_q;
@@ -599,10 +606,11 @@ lcp_status finish_records(lcp_plan_s* P, int R, uint64_t* offs, uint32_t* flags,
 }
 
 RecHdr make_hdr(int mode, int F, int k, int cl, int A, uint64_t n, uint64_t seq, uint64_t ref_seq,
-                const HostGrid* g) {
+                const HostGrid* g, int scale = 1) {
   RecHdr h;
   memset(&h, 0, sizeof(h));
   h.mode = mode;
+  h.scale = scale;
   h.F = F;
   h.k = k;
   h.chunk_log2 = cl;
@@ -806,6 +814,7 @@ lcp_status extent(lcp_plan_s* P, const float* const* x, uint64_t n, float* lo, f
 // residual kernel itself, so no extent pass is needed.
 GridDev t_grid(const RefState& ref, int F) {
   GridDev gd = to_dev(ref.grid, F);
+  gd.scale = ref.scale;
   for (int f = 0; f < F; f++) {
     gd.eb2[f] = 2.0 * ref.grid[f].eb;
     gd.lim[f] = ldexp(1.0, ref.grid[f].E);
@@ -839,7 +848,7 @@ lcp_status launch_t(lcp_plan_s* P, const float* const* x, uint64_t n, const RefS
   B.fused = fused;
   EncRec& rc = P->erec_host[0];
   memset(&rc, 0, sizeof(rc));
-  rc.h = make_hdr(1, F, 0, P->chunk_log2, F, n, seq, ref.seq, ref.grid);
+  rc.h = make_hdr(1, F, 0, P->chunk_log2, F, n, seq, ref.seq, ref.grid, ref.scale);
   rc.a0 = 0;
   lcp_status st;
   // the residual kernel counts field f into spread copies f * kHistCopies ...
@@ -1000,6 +1009,14 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
                 (fr.method == LCP_METHOD_AUTO && (!P->have_last_s || size_t_ > P->last_s));
   SResult sr;
   double eb_f[kMaxF];
+  // Sec. 7.4.2: a frame that would become an anchor (first in its batch, coded
+  // by S) is coded at eb / s while the stream is temporally correlated: at its
+  // start (no frame since an anchor yet), or when at least half of the frames
+  // since the last anchor were coded by T
+  int s_scale = 1;
+  if (multi && P->p.anchor_scale > 1 && first_in_batch(P, P->seq) &&
+      (P->n_since_anchor == 0 || 2 * P->t_since_anchor >= P->n_since_anchor))
+    s_scale = P->p.anchor_scale;
   if (need_s) {
     float lo[kMaxF], hi[kMaxF];
     if ((st = extent(P, fr.fields, n, lo, hi, s))) return st;
@@ -1007,7 +1024,7 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
     else if ((st = field_eb(P->p, F, lo, hi, eb_f))) return st;
     HostGrid sg[kMaxF];
     for (int f = 0; f < F; f++)
-      if ((st = make_grid(lo[f], hi[f], eb_f[f], &sg[f]))) return st;
+      if ((st = make_grid(lo[f], hi[f], eb_f[f] / (double)s_scale, &sg[f]))) return st;
     if (multi) {
       qs_i = free_q(P, qt_i);
       ps_i = free_perm(P);
@@ -1025,6 +1042,7 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
       if (multi) {
         RefState r;
         r.valid = true;
+        r.scale = s_scale;
         r.seq = P->seq;
         r.n = n;
         memcpy(r.grid, sg, sizeof(sg));
@@ -1046,7 +1064,9 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
     HIP_OK(hipMemcpyAsync(out, s_buf, size_s, hipMemcpyDeviceToDevice, s));
   *size = chosen;
   if (used) *used = chose_t ? LCP_METHOD_T : LCP_METHOD_S;
-  if (have_s) {
+  // the estimate of S is an S record at the stream's bound; an anchor coded at
+  // eb / s stands in only until there is one
+  if (have_s && (s_scale == 1 || !P->have_last_s)) {
     P->last_s = size_s;
     P->have_last_s = true;
   }
@@ -1071,6 +1091,13 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
   if (perm_out) {
     const uint32_t* src = chose_t ? P->ppool[P->prev.perm] : (multi ? P->ppool[ps_i] : sr.perm);
     launch_copy_perm(src, perm_out, n, s);
+  }
+  if (!chose_t && first_in_batch(P, P->seq)) {
+    P->n_since_anchor = 0;
+    P->t_since_anchor = 0;
+  } else {
+    P->n_since_anchor++;
+    P->t_since_anchor += chose_t ? 1 : 0;
   }
   P->seq++;
   return LCP_OK;
@@ -1179,7 +1206,8 @@ lcp_status run_t(lcp_plan_s* P, const lcp_frame_in* fr, int D, const RunFrame* r
   for (int k = 0; k < D; k++) {
     EncRec& rc = P->erec_host[k];
     memset(&rc, 0, sizeof(rc));
-    rc.h = make_hdr(1, F, 0, P->chunk_log2, F, n, P->seq + k, rf[k].ref.seq, rf[k].ref.grid);
+    rc.h = make_hdr(1, F, 0, P->chunk_log2, F, n, P->seq + k, rf[k].ref.seq, rf[k].ref.grid,
+                    rf[k].ref.scale);
     rc.a0 = (uint32_t)B.NA;
     for (int f = 0; f < F; f++) {
       const uint64_t a = (uint64_t)k * F + f;
@@ -1216,6 +1244,8 @@ lcp_status run_t(lcp_plan_s* P, const lcp_frame_in* fr, int D, const RunFrame* r
     r.q = rf[c].q;
     P->prev = r;
     if (perms && perms[c]) launch_copy_perm(P->ppool[r.perm], perms[c], fr[c].n, s);
+    P->n_since_anchor++;
+    P->t_since_anchor++;
     P->seq++;
     ends[c] = ho[c + 1];
   }
@@ -1223,10 +1253,18 @@ lcp_status run_t(lcp_plan_s* P, const lcp_frame_in* fr, int D, const RunFrame* r
   P->run_len = c < D ? kTRunStart : (D == P->run_len && D < kTRun ? 2 * D : P->run_len);
   // only the last frame of each segment left its codes, and a later segment
   // may have reused that slot: after a break, the last committed frame's codes
-  // are rebuilt from its input
+  // are rebuilt from its input (and, on a scaled grid, from the frames of its
+  // segment before it, starting at the segment's reference, whose slot the run
+  // never writes: the run's starting reference or the anchor)
   if (c >= 1 && c < D) {
-    launch_t_codes(field_ptrs(fr[c - 1].fields, F), F, fr[c - 1].n, t_grid(P->prev, F),
-                   P->ppool[P->prev.perm], P->qpool[P->prev.q], P->err, s);
+    int k0 = c - 1;
+    while (k0 > 0 && rf[k0].chain) k0--;
+    RunFrames rx;
+    memset(&rx, 0, sizeof(rx));
+    for (int j = k0; j < c; j++)
+      for (int f = 0; f < F; f++) rx.x[j - k0][f] = fr[j].fields[f];
+    launch_t_codes(rx, c - k0, F, fr[c - 1].n, t_grid(P->prev, F), P->ppool[P->prev.perm],
+                   P->qpool[rf[k0].ref.q], P->qpool[P->prev.q], P->err, s);
     P->err_clean = false;
   }
   return LCP_OK;
@@ -1235,6 +1273,7 @@ lcp_status run_t(lcp_plan_s* P, const lcp_frame_in* fr, int D, const RunFrame* r
 // ------------------------------------------------------------------ decode
 struct ParsedHdr {
   int mode, F, k, cl, A;
+  int scale;  // temporal records: residual step (Sec. 7.4.2); 1 for spatial ones
   uint64_t n, B, total, seq, ref_seq;
   uint32_t bn[3];
   float m[kMaxF], eb_q[kMaxF];
@@ -1262,6 +1301,8 @@ lcp_status parse_header(const uint8_t* b, uint64_t size, ParsedHdr* h) {
   h->k = b[8];
   h->cl = b[9];
   h->A = b[10];
+  h->scale = b[11] ? b[11] : 1;
+  if ((h->mode == 0 && b[11] != 0) || h->scale > 15 || h->scale % 2 == 0) return LCP_ERR_CORRUPT;
   if (h->mode > 1 || h->F < 3 || h->F > kMaxF || h->k > 16 || h->cl < 5 || h->cl > 16)
     return LCP_ERR_CORRUPT;
   int A = h->mode == 0 ? h->F + 2 : h->F;
@@ -1586,6 +1627,7 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
       const uint8_t* rec = reinterpret_cast<const uint8_t*>(blobs[j].data);
       GridDev gd;
       memset(&gd, 0, sizeof(gd));
+      gd.scale = h.scale;
       for (int f = 0; f < F; f++) {
         gd.m[f] = h.m[f];
         gd.eb_q[f] = h.eb_q[f];
@@ -2066,7 +2108,8 @@ lcp_status plan_check(const lcp_params& p, const float* const* sample_fields, ui
       p.max_particles > (1ull << 31) || !(p.eb > 0) || p.eb_mode < 0 || p.eb_mode > 2 ||
       p.max_batch_frames < 0 || p.max_batch_frames > kMaxBatch ||
       (p.max_batch_particles != 0 &&
-       (p.max_batch_particles < p.max_particles || p.max_batch_particles > 0xFFFFFFFFull)))
+       (p.max_batch_particles < p.max_particles || p.max_batch_particles > 0xFFFFFFFFull)) ||
+      p.anchor_scale < 0 || p.anchor_scale > 15 || (p.anchor_scale > 1 && p.anchor_scale % 2 == 0))
     return LCP_ERR_ARG;
   if (p.block_log2 == -1 && (!sample_fields || sample_n == 0 || sample_n > p.max_particles))
     return LCP_ERR_ARG;
@@ -2113,7 +2156,7 @@ namespace lcp {
 bool ktimer_events(const char* name, uint64_t bytes, hipEvent_t* start, hipEvent_t* stop) {
   lcp_plan_s* P = g_timer_plan;
   if (!P || P->capturing || !P->timer_name[0] || strcmp(P->timer_name, name) != 0) return false;
-  if (P->timer_seen++ % kTimerStride != 0) return false;
+  if (P->timer_seen++ % P->timer_every != 0) return false;
   *start = timer_event(P);
   *stop = timer_event(P);
   P->ev_pending.push_back({*start, *stop});
@@ -2221,6 +2264,8 @@ lcp_status lcp_plan_reset(lcp_plan_t plan) {
   plan->untested = 0;
   plan->last_s = 0;
   plan->have_last_s = false;
+  plan->n_since_anchor = 0;
+  plan->t_since_anchor = 0;
   return LCP_OK;
 }
 
@@ -2404,11 +2449,22 @@ lcp_status lcp_plan_autotune(lcp_plan_t plan, uint64_t n_frames, const lcp_frame
 
 lcp_status lcp_kernel_timer_set(lcp_plan_t plan, const char* kernel_name) {
   if (!plan) return LCP_ERR_ARG;
+  plan->timer_every = kTimerStride;
   if (!kernel_name) {
     plan->timer_name[0] = 0;
   } else {
-    if (strlen(kernel_name) >= sizeof(plan->timer_name)) return LCP_ERR_ARG;
-    strcpy(plan->timer_name, kernel_name);
+    // "name" or "name/N": one launch in N (1..1024) is timed
+    const char* slash = strchr(kernel_name, '/');
+    const size_t len = slash ? (size_t)(slash - kernel_name) : strlen(kernel_name);
+    if (len == 0 || len >= sizeof(plan->timer_name)) return LCP_ERR_ARG;
+    if (slash) {
+      char* end = nullptr;
+      const long every = strtol(slash + 1, &end, 10);
+      if (!end || *end || every < 1 || every > 1024) return LCP_ERR_ARG;
+      plan->timer_every = (uint64_t)every;
+    }
+    memcpy(plan->timer_name, kernel_name, len);
+    plan->timer_name[len] = 0;
   }
   plan->timer_ms = 0;
   plan->timer_launches = 0;
@@ -2536,7 +2592,8 @@ lcp_status serve_t_compress(lcp_plan_s* B, int K, lcp_plan_s* const* plans,
     const uint64_t n = frames[i].n;
     EncRec& rc = B->erec_host[i];
     memset(&rc, 0, sizeof(rc));
-    rc.h = make_hdr(1, F, 0, B->chunk_log2, F, n, plans[i]->seq, refs[i].seq, refs[i].grid);
+    rc.h = make_hdr(1, F, 0, B->chunk_log2, F, n, plans[i]->seq, refs[i].seq, refs[i].grid,
+                    refs[i].scale);
     rc.a0 = (uint32_t)EB.NA;
     for (int f = 0; f < F; f++) {
       const uint64_t a = (uint64_t)i * F + f;
@@ -2578,6 +2635,8 @@ lcp_status serve_t_compress(lcp_plan_s* B, int K, lcp_plan_s* const* plans,
     r.seq = P->seq;
     r.q = qsel[i];
     P->prev = r;
+    P->n_since_anchor++;
+    P->t_since_anchor++;
     P->seq++;
     sizes[i] = size;
     done[i] = true;
@@ -2646,6 +2705,7 @@ lcp_status serve_t_decompress(lcp_plan_s* B, int K, lcp_plan_s* const* plans,
     memset(&t, 0, sizeof(t));
     t.q_ref = P->dqpool[refq];
     t.q_new = P->dqpool[dq[i]];
+    t.scale = h.scale;
     t.r8 = reinterpret_cast<const int8_t*>(B->dres8 + (uint64_t)F * off);
     for (int f = 0; f < F; f++) {
       t.out[f] = dsts[i].fields[f];

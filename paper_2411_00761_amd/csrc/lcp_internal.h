@@ -25,6 +25,9 @@ struct GridDev {
   double inv[kMaxF];
   double eb2[kMaxF];  // 2 * the user's bound (temporal feasibility check)
   double lim[kMaxF];  // 2^E: |x| + 2 eb must stay below it on this grid
+  // temporal frames: the step of the codes on this grid (1, or the scale of
+  // the anchor the grid was made for, Sec. 7.4.2)
+  int32_t scale, pad;
 };
 
 // One symbol array to be coded: u64 or u32 values; its length is n, or
@@ -59,6 +62,7 @@ struct ArrWork {
 // Header fields of a record being written.
 struct RecHdr {
   int mode, F, k, chunk_log2, A;
+  int scale;  // temporal records: residual step (byte 11; 1 is written as 0)
   uint64_t n, seq, ref_seq;
   uint32_t bn[3];
   float m[kMaxF], eb_q[kMaxF];
@@ -329,6 +333,7 @@ struct TReconDev {
   float* out[kMaxF];
   uint64_t n;
   float m[kMaxF], eb_q[kMaxF];
+  int32_t scale, pad;
 };
 void launch_t_recon_multi(const TReconDev* frames, const uint32_t* pre, uint32_t blocks, int R,
                           int F, uint32_t* err, uint64_t bytes, hipStream_t s);
@@ -341,9 +346,13 @@ void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, ui
 void launch_s_recon(const uint32_t* blk, const uint32_t* corner, uint64_t B, int F, uint64_t n,
                     int k, const GridDev& g, const OutPtrs& out, int32_t* q_slot, uint32_t* err,
                     hipStream_t s);
-// out.p[f] holds int32 residuals; q_slot receives q_ref + residual.
-void launch_t_codes(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
-                    const uint32_t* perm_ref, int32_t* q_new, uint32_t* err, hipStream_t s);
+// The codes the last of J temporal frames leaves as the next reference: with
+// step 1 (g.scale) they are its own Eq. 5 codes (only frame J - 1 is read,
+// q_ref is unused); with a larger step they follow the chain of frames from
+// the codes q_ref of the frames' first reference.
+void launch_t_codes(const RunFrames& fr, int J, int F, uint64_t n, const GridDev& g,
+                    const uint32_t* perm_ref, const int32_t* q_ref, int32_t* q_new,
+                    uint32_t* err, hipStream_t s);
 void launch_t_recon(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,
                     const OutPtrs& out, int32_t* q_slot, uint32_t* err, hipStream_t s);
 // Copies `bytes` (a multiple of 4) from host memory to device memory through
