@@ -98,6 +98,10 @@ def lib():
                                      C.c_int, C.c_uint64, P, C.c_uint64, C.POINTER(C.c_uint64),
                                      P]
         L.lco_record_info.argtypes = [P, C.c_uint64, C.POINTER(Info)]
+        L.lco_container_pack.argtypes = [P, P, C.c_uint64, C.c_int, P, C.c_uint64,
+                                         C.POINTER(C.c_uint64)]
+        L.lco_container_closure.argtypes = [P, C.c_uint64, C.c_uint64, P, C.c_uint64,
+                                            C.POINTER(C.c_uint64)]
         L.lco_decompress.argtypes = [P, C.c_uint64, P, C.c_uint64, C.c_uint64, P, C.c_uint64,
                                      C.POINTER(C.c_uint64), P]
         L.lco_stream_create.argtypes = [C.POINTER(Params), C.c_uint64]
@@ -323,3 +327,75 @@ class Stream:
         _check(lib().lco_stream_decompress(self.h, _ptr(buf), len(rec), optrs, info.n,
                                            C.byref(nout)), "stream_decompress")
         return outs
+
+
+# ---------------------------------------------------------------- container (Sec. 7.3)
+CONTAINER_HDR, CONTAINER_ENTRY = 64, 32
+
+
+def container_pack(records, batch_size: int) -> bytes:
+    """Records of one stream (frames 0..n-1 in order) packed for random access."""
+    bufs = [np.frombuffer(r, np.uint8).copy() for r in records]
+    n = len(bufs)
+    ptrs = (C.c_void_p * n)(*[b.ctypes.data for b in bufs])
+    sizes = np.array([len(r) for r in records], np.uint64)
+    size = C.c_uint64()
+    _check(lib().lco_container_pack(ptrs, _ptr(sizes), n, batch_size, None, 0, C.byref(size)),
+           "container_pack")
+    out = np.zeros(size.value, np.uint8)
+    _check(lib().lco_container_pack(ptrs, _ptr(sizes), n, batch_size, _ptr(out), size.value,
+                                    C.byref(size)), "container_pack")
+    return out.tobytes()
+
+
+def container_closure(cont: bytes, k: int):
+    buf = np.frombuffer(cont, np.uint8).copy()
+    frames = np.zeros(1 << 16, np.uint64)
+    count = C.c_uint64()
+    _check(lib().lco_container_closure(_ptr(buf), len(cont), k, _ptr(frames), len(frames),
+                                       C.byref(count)), "container_closure")
+    return [int(v) for v in frames[: count.value]]
+
+
+def container_entries(cont: bytes):
+    """(frames, batch_size, [(offset, size, ref_seq, n, mode, anchor)])"""
+    import struct
+    n = struct.unpack_from("<Q", cont, 16)[0]
+    batch = struct.unpack_from("<I", cont, 8)[0]
+    ents = [struct.unpack_from("<QQQIBB", cont, CONTAINER_HDR + CONTAINER_ENTRY * j)
+            for j in range(n)]
+    return n, batch, ents
+
+
+def container_passes(frames):
+    """Requests in the caller's order, split into passes of increasing frame
+    numbers: each pass decodes the union of its requests' closures in stream
+    order on a fresh decoder."""
+    passes, cur = [], []
+    for k in frames:
+        if cur and k <= cur[-1]:
+            passes.append(cur)
+            cur = []
+        cur.append(k)
+    if cur:
+        passes.append(cur)
+    return passes
+
+
+def container_retrieve(cont: bytes, frames, eb_mode, eb, n_fields=3, block_log2=4,
+                       anchor_scale=0):
+    """{frame: decoded fields [F][n] in slot order} for the requested frames, and
+    the number of records decoded."""
+    n, batch, ents = container_entries(cont)
+    out, decoded = {}, 0
+    for ps in container_passes(frames):
+        need = sorted(set(j for k in ps for j in container_closure(cont, k)))
+        st = Stream(eb_mode, eb, n_fields=n_fields, batch_size=batch, block_log2=block_log2,
+                    max_n=max(e[3] for e in ents), anchor_scale=anchor_scale)
+        for j in need:
+            off, size = ents[j][0], ents[j][1]
+            dec = st.decompress(cont[off:off + size])
+            decoded += 1
+            if j in ps:
+                out[j] = dec
+    return out, decoded

@@ -1191,6 +1191,108 @@ int lco_stream_decompress(lco_stream* s, const uint8_t* rec, uint64_t size,
 }
 
 /* ------------------------------------------------------------------ */
+/* multi-frame container: Sec. 7.3 stores the anchor frames (first in    */
+/* their batch, coded by LCP-S) in an array of their own and retrieves a */
+/* frame by locating it in its batch or the anchor array, decoding its   */
+/* reference first when it is temporal                                  */
+/* ------------------------------------------------------------------ */
+#define CMAGIC 0x4350434Cu /* bytes "LCPC" */
+
+int lco_container_pack(const uint8_t* const* recs, const uint64_t* sizes, uint64_t n,
+                       int batch_size, uint8_t* out, uint64_t cap, uint64_t* size) {
+  if (n == 0 || batch_size < 0 || !recs || !sizes) return LCO_ERR_ARG;
+  lco_info* I = (lco_info*)malloc(sizeof(lco_info) * n);
+  int st = LCO_OK;
+  for (uint64_t j = 0; j < n && st == LCO_OK; j++) {
+    st = lco_record_info(recs[j], sizes[j], &I[j]);
+    /* one stream from its start: record j is frame j, references go back */
+    if (st == LCO_OK && (I[j].seq != j || I[j].total_bytes != sizes[j] || I[j].F != I[0].F ||
+                         (I[j].mode == 1 && I[j].ref_seq >= j)))
+      st = LCO_ERR_ARG;
+  }
+  if (st) {
+    free(I);
+    return st;
+  }
+  /* where each record goes: batch arrays first, the anchor array last */
+  uint64_t off = LCO_CONTAINER_HDR + LCO_CONTAINER_ENTRY * n, anchors = 0;
+  uint64_t* where = (uint64_t*)malloc(sizeof(uint64_t) * n);
+  int* is_anchor = (int*)malloc(sizeof(int) * n);
+  for (uint64_t j = 0; j < n; j++) {
+    int first = batch_size == 0 ? j == 0 : j % (uint64_t)batch_size == 0;
+    is_anchor[j] = first && I[j].mode == 0;
+    anchors += is_anchor[j];
+    if (!is_anchor[j]) {
+      where[j] = off;
+      off += sizes[j];
+    }
+  }
+  uint64_t anchor_off = off;
+  for (uint64_t j = 0; j < n; j++)
+    if (is_anchor[j]) {
+      where[j] = off;
+      off += sizes[j];
+    }
+  *size = off;
+  if (out) {
+    if (off > cap) {
+      st = LCO_ERR_CAPACITY;
+    } else {
+      memset(out, 0, LCO_CONTAINER_HDR + LCO_CONTAINER_ENTRY * n);
+      put_u32(out + 0, CMAGIC);
+      put_u16(out + 4, 1);
+      put_u32(out + 8, (uint32_t)batch_size);
+      put_u32(out + 12, (uint32_t)I[0].F);
+      put_u64(out + 16, n);
+      put_u64(out + 24, anchors);
+      put_u64(out + 32, LCO_CONTAINER_HDR);
+      put_u64(out + 40, anchor_off);
+      put_u64(out + 48, off);
+      for (uint64_t j = 0; j < n; j++) {
+        uint8_t* e = out + LCO_CONTAINER_HDR + LCO_CONTAINER_ENTRY * j;
+        put_u64(e + 0, where[j]);
+        put_u64(e + 8, sizes[j]);
+        put_u64(e + 16, I[j].mode == 1 ? I[j].ref_seq : UINT64_MAX);
+        put_u32(e + 24, (uint32_t)I[j].n);
+        put_u8(e + 28, (unsigned)I[j].mode);
+        put_u8(e + 29, (unsigned)is_anchor[j]);
+        memcpy(out + where[j], recs[j], sizes[j]);
+      }
+    }
+  }
+  free(where);
+  free(is_anchor);
+  free(I);
+  return st;
+}
+
+int lco_container_closure(const uint8_t* cont, uint64_t size, uint64_t k, uint64_t* frames,
+                          uint64_t cap, uint64_t* count) {
+  if (size < LCO_CONTAINER_HDR || get_u32(cont) != CMAGIC) return LCO_ERR_CORRUPT;
+  uint64_t n = get_u64(cont + 16);
+  if (n > (size - LCO_CONTAINER_HDR) / LCO_CONTAINER_ENTRY) return LCO_ERR_CORRUPT;
+  if (k >= n) return LCO_ERR_ARG;
+  /* walk the references back to a spatial frame, then list them in order */
+  uint64_t c = 0, j = k;
+  for (;;) {
+    if (c >= cap) return LCO_ERR_CAPACITY;
+    frames[c++] = j;
+    const uint8_t* e = cont + LCO_CONTAINER_HDR + LCO_CONTAINER_ENTRY * j;
+    if (e[28] == 0) break;
+    uint64_t r = get_u64(e + 16);
+    if (r >= j) return LCO_ERR_CORRUPT;
+    j = r;
+  }
+  for (uint64_t a = 0, b = c - 1; a < b; a++, b--) {
+    uint64_t t = frames[a];
+    frames[a] = frames[b];
+    frames[b] = t;
+  }
+  *count = c;
+  return LCO_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* a12: block-size search on a stride sample                           */
 /* ------------------------------------------------------------------ */
 int lco_search_k(const float* const* x, int F, uint64_t n, const lco_params* p, int* k_out,

@@ -131,6 +131,19 @@ int lco_search_k(const float* const* x, int F, uint64_t n, const lco_params* p,
 
 uint64_t lco_bound(int F, uint64_t n, int chunk_log2);
 
+/* ---- multi-frame container (Sec. 7.3, Alg. 1): random access ----
+ * The records of one stream (seq 0..n-1, in order) packed as: a 64-byte header,
+ * a 32-byte entry per frame, the records of each batch in stream order except
+ * the anchors (first-in-batch frames coded by LCP-S), then the anchor array. */
+#define LCO_CONTAINER_HDR 64
+#define LCO_CONTAINER_ENTRY 32
+int lco_container_pack(const uint8_t* const* recs, const uint64_t* sizes, uint64_t n,
+                       int batch_size, uint8_t* out, uint64_t cap, uint64_t* size);
+/* Frames that must be decoded to obtain frame k (k itself, its reference,
+ * recursively, down to a spatial frame), in stream order. */
+int lco_container_closure(const uint8_t* cont, uint64_t size, uint64_t k, uint64_t* frames,
+                          uint64_t cap, uint64_t* count);
+
 #ifdef __cplusplus
 }
 #endif
