@@ -274,6 +274,57 @@ lcp_status lcp_kernel_timer_set(lcp_plan_t plan, const char* kernel_name);
 lcp_status lcp_kernel_timer_read(lcp_plan_t plan, double* total_ms, uint64_t* launches,
                                  uint64_t* bytes);
 
+/* ---- Multi-frame container with random access (Sec. 7.3, Alg. 1) ----
+ *
+ * The records of one multi-frame stream, packed so that any frame can be
+ * retrieved alone.  Layout (little-endian, all in one device buffer): a 64-byte
+ * header ("LCPC", version 1, batch size, fields, frame count, anchor count,
+ * table offset 64, anchor-array offset, total bytes), a 32-byte entry per frame
+ * (record offset, size, reference frame or all ones, particle count, method
+ * 0 = S / 1 = T, anchor flag), the records of each batch in stream order, then
+ * the anchor array: the first-in-batch frames coded by LCP-S, which Sec. 7.3
+ * stores apart.  Retrieving frame k decodes it directly when it is spatial,
+ * else its reference first, recursively: at most the frames of its batch up to
+ * k plus one anchor. */
+typedef struct lcp_container_s* lcp_container_t;
+
+/* Pack n records of one stream (records[j] is frame j, j = 0..n-1, as a
+ * multi-frame lcp_compress wrote them; device pointers, 4-byte aligned) with the
+ * stream's batch size into out (device, out_cap bytes; NULL only sizes it).
+ * *out_size receives the container's size.  Synchronises the stream.
+ * Errors: LCP_ERR_ARG (not one stream from its start, mixed field counts),
+ * LCP_ERR_CORRUPT (not a record), LCP_ERR_CAPACITY, LCP_ERR_DEVICE. */
+lcp_status lcp_container_pack(const lcp_blob* records, uint64_t n, int batch_size, void* out,
+                              uint64_t out_cap, uint64_t* out_size, hipStream_t stream);
+
+/* Open a container in device memory (it must stay alive and unchanged until
+ * lcp_container_close): reads its header and frame table.  Errors: LCP_ERR_ARG,
+ * LCP_ERR_CORRUPT (bad magic, sizes, offsets, references or anchor flags),
+ * LCP_ERR_DEVICE. */
+lcp_status lcp_container_open(const void* container, uint64_t size, hipStream_t stream,
+                              lcp_container_t* out);
+lcp_status lcp_container_info(lcp_container_t c, uint64_t* frames, int* batch_size,
+                              uint64_t* anchors, int* n_fields);
+
+/* The frames that must be decoded to obtain `frame`, in stream order (the last
+ * is `frame`), into frames[0..*count) (LCP_ERR_CAPACITY when cap is smaller). */
+lcp_status lcp_container_closure(lcp_container_t c, uint64_t frame, uint64_t* frames,
+                                 uint64_t cap, uint64_t* count);
+
+/* Retrieve frames[0..n_req) into outs[i] (device, slot order as lcp_decompress
+ * writes them) with a multi-frame plan of the container's field count and batch
+ * size (its decode state is reset).  Requests are served in the given order:
+ * each run of requests with increasing frame numbers is one pass that decodes
+ * the union of their closures once, in stream order; a request that goes back
+ * in the stream starts a new pass.  *decoded (nullable) receives the number of
+ * records decoded.  Frames decoded but not requested go to scratch the
+ * container allocates on first use.  Errors: those of lcp_decompress;
+ * LCP_ERR_ARG (a frame out of range, a plan that does not match). */
+lcp_status lcp_container_retrieve(lcp_container_t c, lcp_plan_t plan, uint64_t n_req,
+                                  const uint64_t* frames, const lcp_frame_out* outs,
+                                  uint64_t* decoded, hipStream_t stream);
+void lcp_container_close(lcp_container_t c);
+
 /* ---- Serving: many multi-frame streams, requests overlapped on one device ----
  *
  * A server holds multi-frame streams (each one the state of a multi-frame plan:

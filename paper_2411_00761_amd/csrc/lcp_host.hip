@@ -2523,6 +2523,9 @@ uint64_t serve_batch_particles(lcp_plan_s* B) { return B->NB; }
 int plan_fields(lcp_plan_s* P) { return P->F; }
 int plan_chunk_log2(lcp_plan_s* P) { return P->chunk_log2; }
 bool plan_decoding_t(lcp_plan_s* P) { return P->p.multi_frame && P->dec_last_t; }
+bool plan_multi_frame(lcp_plan_s* P) { return P->p.multi_frame != 0; }
+int plan_batch_size(lcp_plan_s* P) { return P->p.batch_size; }
+uint64_t plan_max_particles(lcp_plan_s* P) { return P->N; }
 
 // Whether the stream's next compress request can join a merged launch: its
 // frame will be coded by LCP-T (LCP-FSM in its T state, or forced T) against a

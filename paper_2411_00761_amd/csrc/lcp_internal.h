@@ -177,6 +177,9 @@ int plan_fields(lcp_plan_s* P);
 int plan_chunk_log2(lcp_plan_s* P);
 // Whether the stream's last decoded record was LCP-T (its next one likely is).
 bool plan_decoding_t(lcp_plan_s* P);
+bool plan_multi_frame(lcp_plan_s* P);
+int plan_batch_size(lcp_plan_s* P);
+uint64_t plan_max_particles(lcp_plan_s* P);
 // Whether a compress request of the stream can join a merged launch (its frame
 // goes to LCP-T against a resident reference whatever the size comparison).
 bool serve_t_eligible(lcp_plan_s* P, const lcp_frame_in& fr);

@@ -28,7 +28,9 @@ EXPORTED = ["lcp_plan", "lcp_plan_destroy", "lcp_plan_reset", "lcp_plan_block_lo
             "lcp_server_open_stream", "lcp_server_submit", "lcp_server_wait",
             "lcp_scratch_bytes", "lcp_compress_static", "lcp_plan_set_tuning",
             "lcp_plan_get_tuning", "lcp_plan_autotune", "lcp_server_counts",
-            "lcp_server_hold"]
+            "lcp_server_hold", "lcp_container_pack", "lcp_container_open",
+            "lcp_container_info", "lcp_container_closure", "lcp_container_retrieve",
+            "lcp_container_close"]
 REQ_COMPRESS, REQ_DECOMPRESS = 1, 2
 
 
@@ -175,6 +177,15 @@ def lib():
         L.lcp_server_counts.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_uint64),
                                         C.POINTER(C.c_uint64)]
         L.lcp_server_hold.argtypes = [P, C.c_int]
+        L.lcp_container_pack.argtypes = [P, C.c_uint64, C.c_int, P, C.c_uint64,
+                                         C.POINTER(C.c_uint64), P]
+        L.lcp_container_open.argtypes = [P, C.c_uint64, P, C.POINTER(P)]
+        L.lcp_container_info.argtypes = [P, C.POINTER(C.c_uint64), C.POINTER(C.c_int),
+                                         C.POINTER(C.c_uint64), C.POINTER(C.c_int)]
+        L.lcp_container_closure.argtypes = [P, C.c_uint64, P, C.c_uint64, C.POINTER(C.c_uint64)]
+        L.lcp_container_retrieve.argtypes = [P, P, C.c_uint64, P, P, C.POINTER(C.c_uint64), P]
+        L.lcp_container_close.argtypes = [P]
+        L.lcp_container_close.restype = None
         _lib = L
     return _lib
 
@@ -477,3 +488,64 @@ class Server:
         _check(lib().lcp_server_counts(self.h, C.byref(a), C.byref(b), C.byref(c)),
                "lcp_server_counts")
         return {"merged_launches": a.value, "merged_requests": b.value, "requeued": c.value}
+
+
+class Container:
+    """lcp_container_*: a multi-frame stream's records packed for random access
+    (Sec. 7.3).  buf is the container, a uint8 CUDA tensor kept alive here."""
+
+    @staticmethod
+    def pack(buf, offsets, batch_size: int):
+        """Records buf[offsets[j]:offsets[j+1]] (frames 0..n-1 of one stream) -> container tensor."""
+        import torch
+        offsets = [int(o) for o in offsets]
+        blobs, _tab = blob_table(buf.data_ptr(), offsets)
+        n = len(offsets) - 1
+        size = C.c_uint64()
+        _check(lib().lcp_container_pack(blobs, n, batch_size, None, 0, C.byref(size),
+                                        _stream_handle()), "lcp_container_pack")
+        out = torch.empty(size.value, dtype=torch.uint8, device=buf.device)
+        _check(lib().lcp_container_pack(blobs, n, batch_size, C.c_void_p(out.data_ptr()),
+                                        out.numel(), C.byref(size), _stream_handle()),
+               "lcp_container_pack")
+        return out
+
+    def __init__(self, buf):
+        self.buf = buf
+        h = C.c_void_p()
+        _check(lib().lcp_container_open(C.c_void_p(buf.data_ptr()), buf.numel(), _stream_handle(),
+                                        C.byref(h)), "lcp_container_open")
+        self.h = h
+        fr, b, a, F = C.c_uint64(), C.c_int(), C.c_uint64(), C.c_int()
+        _check(lib().lcp_container_info(h, C.byref(fr), C.byref(b), C.byref(a), C.byref(F)),
+               "lcp_container_info")
+        self.frames, self.batch_size, self.anchors, self.F = fr.value, b.value, a.value, F.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().lcp_container_close(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def closure(self, frame: int):
+        arr = (C.c_uint64 * 4096)()
+        cnt = C.c_uint64()
+        _check(lib().lcp_container_closure(self.h, frame, arr, 4096, C.byref(cnt)),
+               "lcp_container_closure")
+        return [int(arr[i]) for i in range(cnt.value)]
+
+    def retrieve(self, plan, frames, outs):
+        """Decode frames (list of ints) into outs (list of (F, n) float32 CUDA tensors);
+        returns the number of records decoded."""
+        n = len(frames)
+        fr = (C.c_uint64 * max(n, 1))(*frames)
+        fo, _o = frame_out_table(outs, self.F)
+        dec = C.c_uint64()
+        _check(lib().lcp_container_retrieve(self.h, plan.h, n, fr, fo, C.byref(dec),
+                                            _stream_handle()), "lcp_container_retrieve")
+        return dec.value
