@@ -47,7 +47,7 @@ class OracleError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("eb_mode", C.c_int), ("eb", C.c_double), ("n_fields", C.c_int),
                 ("multi_frame", C.c_int), ("batch_size", C.c_int), ("block_log2", C.c_int),
-                ("chunk_log2", C.c_int), ("anchor_scale", C.c_int)]
+                ("chunk_log2", C.c_int), ("anchor_scale", C.c_int), ("n_dims", C.c_int)]
 
 
 class Grid(C.Structure):
@@ -63,7 +63,7 @@ class Info(C.Structure):
                 ("coder", C.c_int * (MAX_F + 2)), ("param", C.c_int * (MAX_F + 2)),
                 ("used", C.c_uint32 * (MAX_F + 2)), ("arr_n", C.c_uint64 * (MAX_F + 2)),
                 ("arr_off", C.c_uint64 * (MAX_F + 2)), ("arr_bytes", C.c_uint64 * (MAX_F + 2)),
-                ("scale", C.c_int)]
+                ("scale", C.c_int), ("dims", C.c_int)]
 
 
 _lib = None
@@ -92,7 +92,7 @@ def lib():
                                        C.POINTER(C.c_int), C.POINTER(C.c_uint32)]
         L.lco_decode_array.argtypes = [P, C.c_uint64, C.c_uint64, C.c_int, C.c_int,
                                        C.c_uint32, C.c_int, P]
-        L.lco_compress_s.argtypes = [P, C.c_int, C.c_uint64, P, C.c_int, C.c_int, C.c_uint64,
+        L.lco_compress_s.argtypes = [P, C.c_int, C.c_int, C.c_uint64, P, C.c_int, C.c_int, C.c_uint64,
                                      P, C.c_uint64, C.POINTER(C.c_uint64), P, P]
         L.lco_compress_t.argtypes = [P, C.c_int, C.c_uint64, P, P, P, C.c_uint64, C.c_int,
                                      C.c_int, C.c_uint64, P, C.c_uint64, C.POINTER(C.c_uint64),
@@ -219,7 +219,7 @@ def grids_for(fields, eb_mode, eb):
     return [make_grid(lo[f], hi[f], ebf[f]) for f in range(len(fields))]
 
 
-def compress_s(fields, grids, k, chunk_log2=10, seq=0):
+def compress_s(fields, grids, k, chunk_log2=10, seq=0, dims=3):
     arrs, ptrs = _fields(fields)
     F, n = len(arrs), len(arrs[0])
     cap = bound(F, n, chunk_log2)
@@ -227,7 +227,7 @@ def compress_s(fields, grids, k, chunk_log2=10, seq=0):
     perm = np.zeros(n, np.uint32)
     q = np.zeros((F, n), np.int32)
     size = C.c_uint64()
-    _check(lib().lco_compress_s(ptrs, F, n, _grids(grids), k, chunk_log2, seq, _ptr(out), cap,
+    _check(lib().lco_compress_s(ptrs, F, dims, n, _grids(grids), k, chunk_log2, seq, _ptr(out), cap,
                                 C.byref(size), _ptr(perm), _ptr(q)), "compress_s")
     return out[: size.value].tobytes(), perm, q
 
@@ -273,9 +273,9 @@ def decompress(rec: bytes, ref_q=None, ref_seq=0):
     return outs, q
 
 
-def search_k(fields, eb_mode, eb, chunk_log2=10):
+def search_k(fields, eb_mode, eb, chunk_log2=10, dims=3):
     arrs, ptrs = _fields(fields)
-    p = Params(eb_mode, eb, len(arrs), 0, 0, 0, chunk_log2)
+    p = Params(eb_mode, eb, len(arrs), 0, 0, 0, chunk_log2, 0, dims)
     k = C.c_int()
     sizes = np.zeros(17, np.uint64)
     _check(lib().lco_search_k(ptrs, len(arrs), len(arrs[0]), C.byref(p), C.byref(k),
@@ -287,9 +287,9 @@ class Stream:
     """Alg. 1 multi-frame driver with LCP-FSM (compress and decompress sides)."""
 
     def __init__(self, eb_mode, eb, n_fields=3, multi_frame=1, batch_size=16, block_log2=4,
-                 chunk_log2=10, max_n=1 << 20, anchor_scale=0):
+                 chunk_log2=10, max_n=1 << 20, anchor_scale=0, n_dims=0):
         self.p = Params(eb_mode, eb, n_fields, multi_frame, batch_size, block_log2, chunk_log2,
-                        anchor_scale)
+                        anchor_scale, n_dims)
         self.F = n_fields
         self.max_n = max_n
         self.h = lib().lco_stream_create(C.byref(self.p), max_n)

@@ -6,7 +6,8 @@
  *
  * Each function follows one passage of the paper (arXiv 2411.00761):
  *   quantisation .............. Sec. 6.1, Eq. 5
- *   block id / size ........... Sec. 6.2.1, Eq. 6
+ *   block id / size ........... Sec. 6.2.1, Eq. 6 (over the spatial dimensions, 1 to 3;
+ *                               Sec. 4 allows data of other dimensions)
  *   block triples ............. Sec. 6.2.1 (non-empty blocks: id, count, relative
  *                               position to the block's (0,0,0) corner)
  *   delta coding .............. Sec. 6.2.2 (D_i - D_{i-1} on each array)
@@ -524,12 +525,11 @@ uint64_t lco_bound(int F, uint64_t n, int chunk_log2) {
    * supplementary codes <= 23, temporal residuals <= 25 bits per value. */
   uint64_t b = HDR_BYTES + 8 * (uint64_t)F + DIR_BYTES * (uint64_t)(F + 2);
   b += 4 * words_for_bits(n * 63) + 4 * words_for_bits(n * 33);
-  b += 3 * 4 * words_for_bits(n * 25);
-  if (F > 3) b += (uint64_t)(F - 3) * 4 * words_for_bits(n * 25);
+  b += (uint64_t)F * 4 * words_for_bits(n * 25);
   return b;
 }
 
-static int write_record(int mode, int scale, int F, uint64_t n, uint64_t B, int k,
+static int write_record(int mode, int scale, int dims, int F, uint64_t n, uint64_t B, int k,
                         int chunk_log2, const uint32_t* bn, uint64_t seq, uint64_t ref_seq,
                         const lco_grid* grids, const arr_in* arrs, int A, uint8_t* out,
                         uint64_t cap, uint64_t* size) {
@@ -561,6 +561,7 @@ static int write_record(int mode, int scale, int F, uint64_t n, uint64_t B, int 
   put_u64(out + 24, B);
   put_u64(out + 32, total);
   for (int d = 0; d < 3; d++) put_u32(out + 40 + 4 * d, bn ? bn[d] : 0);
+  put_u8(out + 52, dims == 3 ? 0u : (unsigned)dims); /* spatial dimensions; 0 means 3 */
   put_u64(out + 56, seq);
   put_u64(out + 64, ref_seq);
   for (int f = 0; f < F; f++) {
@@ -602,10 +603,12 @@ static int keyidx_cmp(const void* a, const void* b) {
   return x->idx < y->idx ? -1 : (x->idx > y->idx);
 }
 
-/* bn_d = (qmax_d >> k) + 1; the block-id space must stay below 2^63. */
-static int block_counts(const lco_grid* grids, const float* hi, int k, uint32_t* bn) {
+/* bn_d = (qmax_d >> k) + 1 over the D spatial dimensions (1 for the others);
+ * the block-id space must stay below 2^63. */
+static int block_counts(const lco_grid* grids, const float* hi, int k, int D, uint32_t* bn) {
   unsigned __int128 tot = 1;
-  for (int d = 0; d < 3; d++) {
+  for (int d = 0; d < 3; d++) bn[d] = 1;
+  for (int d = 0; d < D; d++) {
     int64_t qm = lco_quant(hi[d], &grids[d]);
     if (qm < 0 || qm >= Q_LIMIT) return LCO_ERR_RANGE;
     bn[d] = (uint32_t)((qm >> k) + 1);
@@ -615,10 +618,11 @@ static int block_counts(const lco_grid* grids, const float* hi, int k, uint32_t*
   return LCO_OK;
 }
 
-int lco_compress_s(const float* const* x, int F, uint64_t n, const lco_grid* grids,
+int lco_compress_s(const float* const* x, int F, int D, uint64_t n, const lco_grid* grids,
                    int k, int chunk_log2, uint64_t seq, uint8_t* out, uint64_t cap,
                    uint64_t* size, uint32_t* perm_out, int32_t* q_slot) {
-  if (F < 3 || F > LCO_MAX_F || n == 0 || n > ((uint64_t)1 << 31) || k < 0 || k > 16)
+  if (D < 1 || D > 3 || F < D || F > LCO_MAX_F || n == 0 || n > ((uint64_t)1 << 31) || k < 0 ||
+      k > 16)
     return LCO_ERR_ARG;
   float lo[LCO_MAX_F], hi[LCO_MAX_F];
   int st = lco_extent(x, F, n, lo, hi);
@@ -628,15 +632,16 @@ int lco_compress_s(const float* const* x, int F, uint64_t n, const lco_grid* gri
     if (lco_quant(hi[f], &grids[f]) >= Q_LIMIT) return LCO_ERR_RANGE;
   }
   uint32_t bn[3];
-  st = block_counts(grids, hi, k, bn);
+  st = block_counts(grids, hi, k, D, bn);
   if (st) return st;
   uint64_t p = (uint64_t)1 << k;
 
-  /* Eq. 5 then Eq. 6: quantise, block id from q / p, row-major with x fastest */
+  /* Eq. 5 then Eq. 6: quantise, block id from q / p, row-major with x fastest
+   * (a dimension the data does not have contributes block 0) */
   keyidx_t* ki = (keyidx_t*)malloc(sizeof(keyidx_t) * n);
   for (uint64_t i = 0; i < n; i++) {
-    uint64_t b[3];
-    for (int d = 0; d < 3; d++) b[d] = (uint64_t)lco_quant(x[d][i], &grids[d]) >> k;
+    uint64_t b[3] = {0, 0, 0};
+    for (int d = 0; d < D; d++) b[d] = (uint64_t)lco_quant(x[d][i], &grids[d]) >> k;
     ki[i].key = b[0] + (uint64_t)bn[0] * (b[1] + (uint64_t)bn[1] * b[2]);
     ki[i].idx = (uint32_t)i;
   }
@@ -667,7 +672,7 @@ int lco_compress_s(const float* const* x, int F, uint64_t n, const lco_grid* gri
   }
   uint64_t* v_rel[3];
   uint64_t* v_sup[LCO_MAX_F];
-  for (int d = 0; d < 3; d++) {
+  for (int d = 0; d < D; d++) {
     v_rel[d] = (uint64_t*)malloc(sizeof(uint64_t) * n);
     uint64_t prev = 0;
     for (uint64_t s = 0; s < n; s++) {
@@ -677,7 +682,7 @@ int lco_compress_s(const float* const* x, int F, uint64_t n, const lco_grid* gri
       prev = rel;
     }
   }
-  for (int f = 3; f < F; f++) {
+  for (int f = D; f < F; f++) {
     v_sup[f] = (uint64_t*)malloc(sizeof(uint64_t) * n);
     for (uint64_t s = 0; s < n; s++)
       v_sup[f][s] = (uint64_t)lco_quant(x[f][ki[s].idx], &grids[f]);
@@ -687,24 +692,24 @@ int lco_compress_s(const float* const* x, int F, uint64_t n, const lco_grid* gri
   arrs[0].n = B;
   arrs[1].v = v_cnt;
   arrs[1].n = B;
-  for (int d = 0; d < 3; d++) {
+  for (int d = 0; d < D; d++) {
     arrs[2 + d].v = v_rel[d];
     arrs[2 + d].n = n;
   }
-  for (int f = 3; f < F; f++) {
+  for (int f = D; f < F; f++) {
     arrs[2 + f].v = v_sup[f];
     arrs[2 + f].n = n;
   }
-  st = write_record(0, 1, F, n, B, k, chunk_log2, bn, seq, UINT64_MAX, grids, arrs, F + 2, out,
-                    cap, size);
+  st = write_record(0, 1, D, F, n, B, k, chunk_log2, bn, seq, UINT64_MAX, grids, arrs, F + 2,
+                    out, cap, size);
   if (st == LCO_OK && perm_out)
     for (uint64_t s = 0; s < n; s++) perm_out[s] = ki[s].idx;
   if (st == LCO_OK && q_slot)
     for (int f = 0; f < F; f++)
       for (uint64_t s = 0; s < n; s++)
         q_slot[(uint64_t)f * n + s] = (int32_t)lco_quant(x[f][ki[s].idx], &grids[f]);
-  for (int d = 0; d < 3; d++) free(v_rel[d]);
-  for (int f = 3; f < F; f++) free(v_sup[f]);
+  for (int d = 0; d < D; d++) free(v_rel[d]);
+  for (int f = D; f < F; f++) free(v_sup[f]);
   free(v_id);
   free(v_cnt);
   free(ids);
@@ -721,7 +726,7 @@ int lco_compress_t(const float* const* x, int F, uint64_t n, const lco_grid* gri
                    const uint32_t* ref_perm, const int32_t* ref_q, uint64_t ref_seq,
                    int scale, int chunk_log2, uint64_t seq, uint8_t* out, uint64_t cap,
                    uint64_t* size, int32_t* q_slot) {
-  if (F < 3 || F > LCO_MAX_F || n == 0 || n > ((uint64_t)1 << 31)) return LCO_ERR_ARG;
+  if (F < 1 || F > LCO_MAX_F || n == 0 || n > ((uint64_t)1 << 31)) return LCO_ERR_ARG;
   if (scale < 1 || scale > 15 || scale % 2 == 0) return LCO_ERR_ARG;
   if (!ref_perm || !ref_q) return LCO_ERR_NO_REFERENCE;
   float lo[LCO_MAX_F], hi[LCO_MAX_F];
@@ -765,8 +770,8 @@ int lco_compress_t(const float* const* x, int F, uint64_t n, const lco_grid* gri
     }
   }
   if (st == LCO_OK)
-    st = write_record(1, scale, F, n, 0, 0, chunk_log2, NULL, seq, ref_seq, grids, arrs, F, out,
-                      cap, size);
+    st = write_record(1, scale, 3, F, n, 0, 0, chunk_log2, NULL, seq, ref_seq, grids, arrs, F,
+                      out, cap, size);
   for (int f = 0; f < F; f++) free(v[f]);
   return st;
 }
@@ -784,9 +789,12 @@ int lco_record_info(const uint8_t* rec, uint64_t size, lco_info* info) {
   info->chunk_log2 = rec[9];
   info->n_arrays = rec[10];
   info->scale = rec[11] ? rec[11] : 1;
+  info->dims = rec[52] ? rec[52] : 3;
+  if (rec[52] > 2 || (info->mode == 1 && rec[52] != 0)) return LCO_ERR_CORRUPT;
   if ((info->mode == 0 && rec[11] != 0) || info->scale > 15 || info->scale % 2 == 0)
     return LCO_ERR_CORRUPT;
-  if (info->mode > 1 || info->F < 3 || info->F > LCO_MAX_F || info->k > 16 ||
+  if (info->mode > 1 || info->F < (info->mode == 0 ? info->dims : 1) || info->F > LCO_MAX_F ||
+      info->k > 16 ||
       info->chunk_log2 < 5 || info->chunk_log2 > 16)
     return LCO_ERR_CORRUPT;
   int A = info->mode == 0 ? info->F + 2 : info->F;
@@ -872,7 +880,7 @@ int lco_decompress(const uint8_t* rec, uint64_t size, const int32_t* ref_q,
                bz = id / ((uint64_t)I.bn[0] * I.bn[1]);
       uint64_t corner[3] = {bx << I.k, by << I.k, bz << I.k};
       for (int64_t j = 0; j < c; j++, s++) {
-        for (int d = 0; d < 3; d++) {
+        for (int d = 0; d < I.dims; d++) {
           rel[d] = (rel[d] + v[2 + d][s]) & (p - 1);
           uint64_t qq = corner[d] + rel[d];
           if (v[2 + d][s] >= p || qq >= Q_LIMIT) st = LCO_ERR_CORRUPT;
@@ -881,7 +889,7 @@ int lco_decompress(const uint8_t* rec, uint64_t size, const int32_t* ref_q,
       }
     }
     if (st == LCO_OK && s != n) st = LCO_ERR_CORRUPT;
-    for (int f = 3; f < I.F && st == LCO_OK; f++)
+    for (int f = I.dims; f < I.F && st == LCO_OK; f++)
       for (uint64_t t = 0; t < n; t++) {
         if (v[2 + f][t] >= Q_LIMIT) st = LCO_ERR_CORRUPT;
         q[(uint64_t)f * n + t] = (int32_t)v[2 + f][t];
@@ -965,7 +973,8 @@ static void ref_copy(ref_t* dst, const ref_t* src, int F) {
 }
 
 lco_stream* lco_stream_create(const lco_params* p, uint64_t max_n) {
-  if (!p || p->n_fields < 3 || p->n_fields > LCO_MAX_F || p->block_log2 < 0 ||
+  if (!p || p->n_fields < 1 || p->n_fields > LCO_MAX_F || p->block_log2 < 0 || p->n_dims < 0 ||
+      p->n_dims > 3 || p->n_fields < (p->n_dims ? p->n_dims : 3) ||
       p->block_log2 > 16 || p->chunk_log2 < 5 || p->chunk_log2 > 16 || p->batch_size < 0 ||
       max_n == 0 || p->anchor_scale < 0 || p->anchor_scale > 15 ||
       (p->anchor_scale > 1 && p->anchor_scale % 2 == 0))
@@ -1099,7 +1108,8 @@ int lco_stream_compress(lco_stream* s, const float* const* x, uint64_t n, int me
     bs = (uint8_t*)malloc(bound);
     perm_s = (uint32_t*)malloc(sizeof(uint32_t) * n);
     q_s = (int32_t*)malloc(sizeof(int32_t) * n * F);
-    st = lco_compress_s(x, F, n, sg, s->p.block_log2, s->p.chunk_log2, s->seq, bs, bound,
+    st = lco_compress_s(x, F, s->p.n_dims ? s->p.n_dims : 3, n, sg, s->p.block_log2,
+                        s->p.chunk_log2, s->seq, bs, bound,
                         &size_s, perm_s, q_s);
     if (st == LCO_OK) have_s = 1;
   }
@@ -1297,7 +1307,8 @@ int lco_container_closure(const uint8_t* cont, uint64_t size, uint64_t k, uint64
 /* ------------------------------------------------------------------ */
 int lco_search_k(const float* const* x, int F, uint64_t n, const lco_params* p, int* k_out,
                  uint64_t* sizes) {
-  if (F < 3 || F > LCO_MAX_F || n == 0) return LCO_ERR_ARG;
+  const int D = p->n_dims ? p->n_dims : 3;
+  if (D < 1 || D > 3 || F < D || F > LCO_MAX_F || n == 0) return LCO_ERR_ARG;
   uint64_t stride = n >> 20;
   if (stride < 1) stride = 1;
   uint64_t ns = (n + stride - 1) / stride;
@@ -1316,7 +1327,7 @@ int lco_search_k(const float* const* x, int F, uint64_t n, const lco_params* p, 
   uint64_t best_size = 0;
   for (int k = 0; k <= 16 && !st; k++) {
     uint64_t sz = 0;
-    int s2 = lco_compress_s((const float* const*)smp, F, ns, g, k, p->chunk_log2, 0, NULL, 0,
+    int s2 = lco_compress_s((const float* const*)smp, F, D, ns, g, k, p->chunk_log2, 0, NULL, 0,
                             &sz, NULL, NULL);
     if (sizes) sizes[k] = s2 == LCO_OK ? sz : 0;
     if (s2 == LCO_OK && (best < 0 || sz < best_size)) {

@@ -43,13 +43,14 @@ enum { LCO_DECIDE_S = 1, LCO_DECIDE_T = 2, LCO_DECIDE_COMPARE = 3 };
 typedef struct {
   int eb_mode;      /* LCO_EB_* */
   double eb;        /* absolute bound, or the factor applied to the value range */
-  int n_fields;     /* 3 (xyz) .. 8; fields 3.. are supplementary */
+  int n_fields;     /* 1 .. 8: the n_dims spatial coordinates, then supplementary fields */
   int multi_frame;  /* 0: every frame spatial; 1: LCP-FSM chooses S/T */
   int batch_size;   /* Alg. 1 batch length; 0 = one unbounded batch */
   int block_log2;   /* k in [0,16]; p = 2^k quantisation bins per block side */
   int chunk_log2;   /* Huffman chunk = 2^chunk_log2 symbols, in [5,16] */
   int anchor_scale; /* 0 or 1: off; odd 3..15: an anchor frame is coded at eb / anchor_scale
                        while the stream's temporal correlation is high (Sec. 7.4.2) */
+  int n_dims;       /* spatial dimensions 1..3 (0 = 3): the fields that form blocks */
 } lco_params;
 
 /* Quantisation grid of one field (Eq. 5 with the FP32 rounding margin). */
@@ -73,6 +74,7 @@ typedef struct {
   uint32_t used[LCO_MAX_F + 2];
   uint64_t arr_n[LCO_MAX_F + 2], arr_off[LCO_MAX_F + 2], arr_bytes[LCO_MAX_F + 2];
   int scale;           /* T records: code step of the residuals (1, or an anchor's scale) */
+  int dims;            /* S records: spatial dimensions (fields 0..dims-1 form the blocks) */
 } lco_info;
 
 /* ---- step-level entry points (pins and parity at every step) ---- */
@@ -96,7 +98,7 @@ int lco_decode_array(const uint8_t* data, uint64_t nbytes, uint64_t n, int coder
 /* ---- frame-level compressors ---- */
 /* LCP-S.  grids[F] must be made from this frame's extent.  perm (slot -> input
  * index, [n]) and q_slot ([F][n], slot order) are optional outputs. */
-int lco_compress_s(const float* const* x, int F, uint64_t n, const lco_grid* grids,
+int lco_compress_s(const float* const* x, int F, int D, uint64_t n, const lco_grid* grids,
                    int k, int chunk_log2, uint64_t seq, uint8_t* out, uint64_t cap,
                    uint64_t* size, uint32_t* perm, int32_t* q_slot);
 /* LCP-T against a reference (grids, slot permutation, slot-order codes).  scale

@@ -120,8 +120,11 @@ def parse(rec: bytes, arrays: bool = True) -> dict:
     assert off == total
     # byte 11: the step of a temporal record's residuals (0 meaning 1); zero in S records
     assert (flags == 0) if mode == 0 else (flags == 0 or flags % 2 == 1)
+    # byte 52: a spatial record's dimensions (0 meaning 3); zero in T records
+    dims = rec[52] if rec[52] else 3
+    assert rec[52] in (0, 1, 2) and (mode == 0 or rec[52] == 0)
     return dict(mode=mode, F=F, k=k, chunk_log2=cl, n=n, B=B, bn=bn, seq=seq, ref_seq=ref_seq,
-                grids=grids, dirs=dirs, arrays=arrays, scale=flags if flags else 1)
+                grids=grids, dirs=dirs, arrays=arrays, scale=flags if flags else 1, dims=dims)
 
 
 def s_codes(rec: bytes):
@@ -139,6 +142,7 @@ def s_codes(rec: bytes):
         acc_c += unzigzag(P["arrays"][1][b])
         ids.append(acc_id)
         cnts.append(acc_c)
+    D = P["dims"]
     q = [[0] * n for _ in range(F)]
     rel = [0, 0, 0]
     s = 0
@@ -146,12 +150,12 @@ def s_codes(rec: bytes):
         i = ids[b]
         corner = (i % bnx, (i // bnx) % bny, i // (bnx * bny))
         for _ in range(cnts[b]):
-            for d in range(3):
+            for d in range(D):
                 rel[d] = (rel[d] + P["arrays"][2 + d][s]) % p
                 q[d][s] = corner[d] * p + rel[d]
             s += 1
     assert s == n
-    for f in range(3, F):
+    for f in range(D, F):
         q[f] = list(P["arrays"][2 + f])
     return q, ids, cnts, P
 
