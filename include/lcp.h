@@ -68,7 +68,8 @@ typedef struct {
                          value range max(D)-min(D) over all fields (Sec. 4).
                          LCP_EB_REL_PER_FIELD: eb times each field's own range. */
   double eb;          /* > 0 */
-  int n_fields;       /* 3 (x, y, z) .. LCP_MAX_FIELDS; fields 3.. are supplementary */
+  int n_fields;       /* 1 .. LCP_MAX_FIELDS: the n_dims spatial coordinates first, then
+                         supplementary fields (velocities ...) */
   int multi_frame;    /* 0: every frame LCP-S.  1: LCP-FSM picks S or T per frame and
                          the error bound is fixed by the stream's first frame. */
   int batch_size;     /* Alg. 1 batch length (frames); 0 = one unbounded batch */
@@ -92,6 +93,10 @@ typedef struct {
                                    the frames since the last anchor were LCP-T; the
                                    LCP-T frames chained to it keep its finer grid and
                                    move in steps of s (the paper uses s = 5) */
+  int n_dims;                   /* spatial dimensions 1..3 (0 = 3): the fields that form
+                                   the blocks of Eq. 6 (Sec. 4: data of other dimensions);
+                                   at most n_fields; a spatial record carries it in
+                                   header byte 52 (3 written as 0) */
 } lcp_params;
 
 typedef struct lcp_plan_s* lcp_plan_t;

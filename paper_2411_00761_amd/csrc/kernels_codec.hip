@@ -903,7 +903,8 @@ __device__ inline void write_header(const RecHdr& h, uint64_t B, uint64_t size, 
   put64(out, 24, B);
   put64(out, 32, size);
   for (int d = 0; d < 3; d++) put32(out, 40 + 4 * d, h.bn[d]);
-  put32(out, 52, 0u);  // reserved words
+  // byte 52: a spatial record's dimensions (3 written as 0); the rest reserved
+  put32(out, 52, h.mode == 0 && h.dims != 3 ? (uint32_t)h.dims : 0u);
   put64(out, 56, h.seq);
   put64(out, 64, h.ref_seq);
   put64(out, 72, 0ull);

@@ -771,12 +771,13 @@ __global__ __launch_bounds__(kThreads) void k_extent_final_b(const uint32_t* par
   }
 }
 
-// Eq. 5 and Eq. 6 per particle.  vals = index within the frame.  rec holds,
-// per particle in input order, what the slot pass needs of it in one padded
-// record of rw words: the three offsets inside its block (k <= 16 bits each,
-// 16 bits apart, words 0-1) and the codes of the supplementary fields (words
-// 2..F-1), so the slot pass gathers one record per slot instead of F - 2
-// separate values.
+// Eq. 5 and Eq. 6 per particle over the frame's D spatial axes (an axis the
+// data does not have counts block 0).  vals = index within the frame.  rec
+// holds, per particle in input order, what the slot pass needs of it in one
+// padded record of rw words: the D offsets inside its block (k <= 16 bits each,
+// 16 bits apart: word 0 for up to two axes, words 0-1 for three) and then the
+// codes of the supplementary fields, so the slot pass gathers one record per
+// slot instead of separate values.
 // Persistent over the batch's tiles of `tile` slots (tile t of frame r at
 // prefix pre[r]); every element-wise batch kernel below walks its tiles so.
 __global__ __launch_bounds__(kThreads) void k_quant_key_b(const SegDev* S, const uint32_t* pre,
@@ -793,17 +794,26 @@ __global__ __launch_bounds__(kThreads) void k_quant_key_b(const SegDev* S, const
   for (uint32_t j = threadIdx.x; j < tile; j += kThreads) {
     const uint64_t i = i0 + j;
     if (i < n) {
+      const int D = g.D;
       const uint64_t q0 = (uint64_t)quantise(g.x[0][i], g.m[0], g.inv[0]);
-      const uint64_t q1 = (uint64_t)quantise(g.x[1][i], g.m[1], g.inv[1]);
-      const uint64_t q2 = (uint64_t)quantise(g.x[2][i], g.m[2], g.inv[2]);
+      const uint64_t q1 = D > 1 ? (uint64_t)quantise(g.x[1][i], g.m[1], g.inv[1]) : 0;
+      const uint64_t q2 = D > 2 ? (uint64_t)quantise(g.x[2][i], g.m[2], g.inv[2]) : 0;
       const uint64_t b0 = q0 >> k, b1 = q1 >> k, b2 = q2 >> k;
       keys[g.off + i] = b0 + g.bn0 * (b1 + g.bn1 * b2);  // Eq. 6, x fastest
       vals[g.off + i] = (uint32_t)i;
       const uint64_t pr = (q0 & pm) | ((q1 & pm) << 16) | ((q2 & pm) << 32);
       uint32_t w[8] = {(uint32_t)pr, (uint32_t)(pr >> 32), 0, 0, 0, 0, 0, 0};
+      // supplementary field f = D + j goes to word 2 + j with three axes, else
+      // to word 1 + j (the offsets then fit word 0); constant word indices
+      if (D == 3) {
 #pragma unroll
-      for (int f = 3; f < kMaxF; f++)
-        if (f < F) w[f - 1] = (uint32_t)quantise(g.x[f][i], g.m[f], g.inv[f]);
+        for (int j = 0; j < kMaxF - 3; j++)
+          if (3 + j < F) w[2 + j] = (uint32_t)quantise(g.x[3 + j][i], g.m[3 + j], g.inv[3 + j]);
+      } else {
+#pragma unroll
+        for (int j = 0; j < kMaxF - 1; j++)
+          if (D + j < F) w[1 + j] = (uint32_t)quantise(g.x[D + j][i], g.m[D + j], g.inv[D + j]);
+      }
       uint32_t* d = rec + (g.off + i) * (uint64_t)rw;
       if (rw == 2) {
         *reinterpret_cast<uint2*>(d) = make_uint2(w[0], w[1]);
@@ -937,16 +947,30 @@ __global__ __launch_bounds__(kThreads) void k_slot_syms_b(const SegDev* S, const
     const uint32_t i = perm[off + s];
     uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     load_rec(rec, off + i, rw, w);
-    const uint64_t pr = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+    const int D = g.D;
+    const uint64_t pr = (uint64_t)w[0] | (D == 3 ? (uint64_t)w[1] << 32 : 0ull);
     for (int d = 0; d < 3; d++) rel[d][threadIdx.x + 1] = (uint32_t)(pr >> (16 * d)) & 0xFFFFu;
-    for (int f = 3; f < F; f++) v_sup[(uint64_t)(f - 3) * ntot + off + s] = w[f - 1];
+    // supplementary codes in words w0.. (constant indices in each branch)
+    uint32_t sup[kMaxF - 1];
+    if (D == 3) {
+#pragma unroll
+      for (int j = 0; j < kMaxF - 1; j++) sup[j] = j < kMaxF - 2 ? w[2 + (j < kMaxF - 2 ? j : 0)] : 0u;
+    } else {
+#pragma unroll
+      for (int j = 0; j < kMaxF - 1; j++) sup[j] = w[1 + j];
+    }
+#pragma unroll
+    for (int j = 0; j < kMaxF - 1; j++)
+      if (D + j < F) v_sup[(uint64_t)j * ntot + off + s] = sup[j];
     if (q_slot) {
       const uint64_t key = keys[off + s];
       const uint64_t bx = key % g.bn0, rest = key / g.bn0;
       const uint64_t b3[3] = {bx, rest % g.bn1, rest / g.bn1};
-      for (int d = 0; d < 3; d++)
+      for (int d = 0; d < D; d++)
         q_slot[(uint64_t)d * ntot + off + s] = (int32_t)((b3[d] << g.k) + rel[d][threadIdx.x + 1]);
-      for (int f = 3; f < F; f++) q_slot[(uint64_t)f * ntot + off + s] = (int32_t)w[f - 1];
+#pragma unroll
+      for (int j = 0; j < kMaxF - 1; j++)
+        if (D + j < F) q_slot[(uint64_t)(D + j) * ntot + off + s] = (int32_t)sup[j];
     }
   }
   if (threadIdx.x == 0) {
@@ -954,14 +978,14 @@ __global__ __launch_bounds__(kThreads) void k_slot_syms_b(const SegDev* S, const
       rel[0][0] = rel[1][0] = rel[2][0] = 0;
     } else {
       const uint64_t j = off + perm[off + s0 - 1];
-      const uint64_t pr = (uint64_t)rec[j * rw] | ((uint64_t)rec[j * rw + 1] << 32);
+      const uint64_t pr = (uint64_t)rec[j * rw] | (g.D == 3 ? (uint64_t)rec[j * rw + 1] << 32 : 0ull);
       for (int d = 0; d < 3; d++) rel[d][0] = (uint32_t)(pr >> (16 * d)) & 0xFFFFu;
     }
   }
   const uint32_t pm = (1u << g.k) - 1u;
   __syncthreads();
   if (valid)
-    for (int d = 0; d < 3; d++)
+    for (int d = 0; d < g.D; d++)
       v_rel[(uint64_t)d * ntot + off + s] = (rel[d][threadIdx.x + 1] - rel[d][threadIdx.x]) & pm;
   __syncthreads();  // the next tile reuses rel
   }
@@ -1077,8 +1101,8 @@ __global__ __launch_bounds__(kThreads) void k_s_recon_b(const uint32_t* blk, con
       continue;
     }
     for (int f = 0; f < F; f++) {
-      uint64_t q = f < 3 ? (uint64_t)corner[(uint64_t)f * Btot + b] + (v[(uint64_t)f * ntot + gs] & pm)
-                         : (uint64_t)v[(uint64_t)f * ntot + gs];
+      uint64_t q = f < g.D ? (uint64_t)corner[(uint64_t)f * Btot + b] + (v[(uint64_t)f * ntot + gs] & pm)
+                           : (uint64_t)v[(uint64_t)f * ntot + gs];
       if (q >= (uint64_t)kQLimit) {
         bad = true;
         q = 0;
@@ -1121,7 +1145,7 @@ __global__ __launch_bounds__(kThreads) void k_s_blocks(const uint64_t* ids,
 }
 
 __global__ __launch_bounds__(kThreads) void k_s_recon(const uint32_t* blk, const uint32_t* corner,
-                                                      uint64_t B, int F, uint64_t n, int k,
+                                                      uint64_t B, int F, int D, uint64_t n, int k,
                                                       GridDev g, OutPtrs out, int32_t* q_slot,
                                                       uint32_t* err) {
   const uint32_t pm = (1u << k) - 1u;
@@ -1135,7 +1159,7 @@ __global__ __launch_bounds__(kThreads) void k_s_recon(const uint32_t* blk, const
     for (int f = 0; f < F; f++) {
       uint32_t* cell = reinterpret_cast<uint32_t*>(out.p[f]) + s;
       uint64_t q;
-      if (f < 3) q = (uint64_t)corner[(uint64_t)f * B + b] + (*cell & pm);
+      if (f < D) q = (uint64_t)corner[(uint64_t)f * B + b] + (*cell & pm);
       else q = *cell;
       if (q >= (uint64_t)kQLimit) {
         atomicOr(err, kErrCorrupt);
@@ -1367,16 +1391,19 @@ void launch_extent_b(const SegDev* S, const uint32_t* pre_ext, uint32_t ext_bloc
   k_extent_final_b<<<dim3(R, F), kThreads, 0, s>>>(part, pre_ext, R, F, ext_blocks, ext);
 }
 
-int slot_rec_words(int F) { return F == 3 ? 2 : (F <= 5 ? 4 : 8); }
+int slot_rec_words(int F, int D) {
+  const int w = (D == 3 ? 2 : 1) + (F - D);  // offsets, then supplementary codes
+  return w <= 2 ? 2 : (w <= 4 ? 4 : 8);
+}
 
 inline uint32_t persistent_grid(uint32_t tiles, uint32_t grid) {
   return grid && grid < tiles ? grid : (tiles ? tiles : 1);
 }
 
 void launch_quant_key_b(const SegDev* S, const uint32_t* pre_tile, const TileShape& ts, int R,
-                        int F, uint64_t* keys, uint32_t* vals, uint32_t* rec, uint64_t ntot,
+                        int F, int D, uint64_t* keys, uint32_t* vals, uint32_t* rec, uint64_t ntot,
                         hipStream_t s) {
-  const int rw = slot_rec_words(F);
+  const int rw = slot_rec_words(F, D);
   launch_timed("quant_key", ntot * (4ull * F + 12 + 4ull * rw), k_quant_key_b,
                persistent_grid(ts.tiles, ts.grid), kThreads, 0, s, S, pre_tile, R, F, ts.tile,
                ts.tiles, keys, vals, rec, rw);
@@ -1401,10 +1428,10 @@ void launch_block_syms_b(const uint64_t* ids, const uint32_t* starts, const uint
 }
 
 void launch_slot_syms_b(const SegDev* S, const uint32_t* pre_256, uint32_t tiles, uint32_t grid,
-                        int R, int F, const uint32_t* perm, const uint64_t* keys,
+                        int R, int F, int D, const uint32_t* perm, const uint64_t* keys,
                         const uint32_t* rec, uint64_t ntot, uint32_t* v_rel, uint32_t* v_sup,
                         int32_t* q_slot, hipStream_t s) {
-  const int rw = slot_rec_words(F);
+  const int rw = slot_rec_words(F, D);
   uint64_t bytes = ntot * (4 + 4ull * rw + 4ull * F + (q_slot ? 8 + 4ull * F : 0));
   launch_timed("slot_syms", bytes, k_slot_syms_b, persistent_grid(tiles, grid), kThreads, 0, s,
                S, pre_256, R, F, perm, keys, rec, rw, ntot, v_rel, v_sup, q_slot, tiles);
@@ -1551,6 +1578,8 @@ void launch_t_resid_run(const RunFrames& fr, int J, int F, uint64_t n, const Gri
   // stay in registers from frame to frame
   auto* kernel = k_t_resid_run<3>;
   switch (F) {
+    case 1: kernel = k_t_resid_run<1>; break;
+    case 2: kernel = k_t_resid_run<2>; break;
     case 4: kernel = k_t_resid_run<4>; break;
     case 5: kernel = k_t_resid_run<5>; break;
     case 6: kernel = k_t_resid_run<6>; break;
@@ -1599,11 +1628,11 @@ void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, ui
       ids, cnt, cum, B, n, total_blocks, bn[0], bn[1], k, corner, mark, err);
 }
 
-void launch_s_recon(const uint32_t* blk, const uint32_t* corner, uint64_t B, int F, uint64_t n,
+void launch_s_recon(const uint32_t* blk, const uint32_t* corner, uint64_t B, int F, int D, uint64_t n,
                     int k, const GridDev& g, const OutPtrs& out, int32_t* q_slot, uint32_t* err,
                     hipStream_t s) {
   launch_timed("s_recon", n * (4 + 12 + 8ull * F + (q_slot ? 4ull * F : 0)), k_s_recon, grid_for(n, kThreads * 4, 1u << 16), kThreads, 0, s,
-               blk, corner, B, F, n, k, g, out, q_slot, err);
+               blk, corner, B, F, D, n, k, g, out, q_slot, err);
 }
 
 void launch_t_recon(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,

@@ -172,7 +172,7 @@ lcp_status lcp_container_open(const void* container, uint64_t size, hipStream_t 
     return LCP_ERR_DEVICE;
   const uint64_t n = rd64(h, 16);
   if (rd32(h, 0) != kCMagic || rd32(h, 4) != 1u || n == 0 || rd64(h, 32) != kCHdr ||
-      n > (size - kCHdr) / kCEntry || rd64(h, 48) != size || rd32(h, 12) < 3 ||
+      n > (size - kCHdr) / kCEntry || rd64(h, 48) != size || rd32(h, 12) < 1 ||
       rd32(h, 12) > LCP_MAX_FIELDS || rd32(h, 8) > 0x7FFFFFFFu)
     return LCP_ERR_CORRUPT;
   std::vector<uint8_t> tab(kCEntry * n);

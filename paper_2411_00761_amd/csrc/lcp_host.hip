@@ -217,6 +217,7 @@ struct lcp_plan_s {
   uint64_t last_s = 0;
   bool have_last_s = false;
   bool dec_last_t = false;  // the last record decoded was LCP-T
+  int D = 3;  // spatial dimensions: fields 0..D-1 form the blocks (Eq. 6)
   // frames coded since the last anchor, and how many of them by LCP-T (the
   // temporal-correlation gate of the anchor scale, Sec. 7.4.2)
   uint64_t n_since_anchor = 0, t_since_anchor = 0;
@@ -349,8 +350,7 @@ uint64_t bound_bytes(int F, uint64_t n) {
   auto words = [](uint64_t bits) { return (bits + 31) / 32; };
   uint64_t b = kHdrBytes + 8ull * F + (uint64_t)kDirBytes * (F + 2);
   b += 4 * words(n * 63) + 4 * words(n * 33);
-  b += 3 * 4 * words(n * 25);
-  if (F > 3) b += (uint64_t)(F - 3) * 4 * words(n * 25);
+  b += (uint64_t)F * 4 * words(n * 25);
   return b;
 }
 
@@ -606,11 +606,12 @@ lcp_status finish_records(lcp_plan_s* P, int R, uint64_t* offs, uint32_t* flags,
 }
 
 RecHdr make_hdr(int mode, int F, int k, int cl, int A, uint64_t n, uint64_t seq, uint64_t ref_seq,
-                const HostGrid* g, int scale = 1) {
+                const HostGrid* g, int scale = 1, int dims = 3) {
   RecHdr h;
   memset(&h, 0, sizeof(h));
   h.mode = mode;
   h.scale = scale;
+  h.dims = dims;
   h.F = F;
   h.k = k;
   h.chunk_log2 = cl;
@@ -664,10 +665,12 @@ lcp_status compress_s_batch(lcp_plan_s* P, int R, const HostGrid (*g)[kMaxF],
     SegDev& sg = P->seg_host[r];
     uint64_t bn[3];
     unsigned __int128 tot = 1;
+    const int D = P->D;
+    bn[0] = bn[1] = bn[2] = 1;  // an axis the data does not have: one block
     for (int f = 0; f < F; f++) {
       int64_t qm = host_quant(hi[r][f], g[r][f]);
       if (qm >= kQLimit) return LCP_ERR_RANGE;
-      if (f < 3) {
+      if (f < D) {
         bn[f] = (uint64_t)((qm >> k) + 1);
         tot *= bn[f];
       }
@@ -680,7 +683,8 @@ lcp_status compress_s_batch(lcp_plan_s* P, int R, const HostGrid (*g)[kMaxF],
     sg.bn0 = bn[0];
     sg.bn1 = bn[1];
     sg.k = k;
-    hdr[r] = make_hdr(0, F, k, P->chunk_log2, F + 2, sg.n, seq0 + r, ~0ull, g[r]);
+    sg.D = D;
+    hdr[r] = make_hdr(0, F, k, P->chunk_log2, F + 2, sg.n, seq0 + r, ~0ull, g[r], 1, D);
     for (int d = 0; d < 3; d++) hdr[r].bn[d] = (uint32_t)bn[d];
   }
   int sort_bits = 0;
@@ -691,8 +695,8 @@ lcp_status compress_s_batch(lcp_plan_s* P, int R, const HostGrid (*g)[kMaxF],
   lcp_status st = upload_segs(P, R, &L, s);
   if (st) return st;
   const uint64_t ntot = L.ntot;
-  uint32_t* v_rel = P->v_slot;
-  uint32_t* v_sup = P->v_slot + 3 * ntot;
+  uint32_t* v_rel = P->v_slot;                       // fields 0..D-1
+  uint32_t* v_sup = P->v_slot + (uint64_t)P->D * ntot;  // fields D..F-1
   EncBuild B;
   B.R = R;
   for (int r = 0; r < R; r++) {
@@ -705,11 +709,11 @@ lcp_status compress_s_batch(lcp_plan_s* P, int R, const HostGrid (*g)[kMaxF],
     rc.a0 = (uint32_t)B.NA;
     if ((st = enc_add(P, B, ArrIn{P->v_id + o, 1, P->Bs + r, n}, n, r, -1, 0))) return st;
     if ((st = enc_add(P, B, ArrIn{P->v_cnt + o, 1, P->Bs + r, n}, n, r, -1, 0))) return st;
-    for (int d = 0; d < 3; d++)
+    for (int d = 0; d < P->D; d++)
       if ((st = enc_add(P, B, ArrIn{v_rel + (uint64_t)d * ntot + o, 0, nullptr, n}, n, r, -1, 0)))
         return st;
-    for (int f = 3; f < F; f++)
-      if ((st = enc_add(P, B, ArrIn{v_sup + (uint64_t)(f - 3) * ntot + o, 0, nullptr, n}, n, r, -1, 0)))
+    for (int f = P->D; f < F; f++)
+      if ((st = enc_add(P, B, ArrIn{v_sup + (uint64_t)(f - P->D) * ntot + o, 0, nullptr, n}, n, r, -1, 0)))
         return st;
   }
   EncLaunch EL;
@@ -732,14 +736,15 @@ lcp_status compress_s_batch(lcp_plan_s* P, int R, const HostGrid (*g)[kMaxF],
   const uint32_t* pre_256 = P->segpre_dev + 2 * (R + 1);
   const TileShape ts{P->tune.tile, L.blocks_1k, P->tune.grid};
   auto kernels = [&](hipStream_t q) {
-    launch_quant_key_b(P->seg_dev, pre_tile, ts, R, F, P->keys0, P->vals0, P->slot_rec, ntot, q);
+    launch_quant_key_b(P->seg_dev, pre_tile, ts, R, F, P->D, P->keys0, P->vals0, P->slot_rec,
+                       ntot, q);
     uint32_t* tmp32 = reinterpret_cast<uint32_t*>(P->scan_tmp);
     radix_sort(P->keys0, P->vals0, P->keys1, P->vals1, P->seg_dev, P->segpre_dev + 3 * (R + 1),
                L.tiles, R, ntot, sort_bits, P->hist, tmp32, q);
     launch_runs_b(keys, P->seg_dev, pre_tile, ts, R, ntot, P->flags, P->ids, P->starts, P->rstart,
                   P->Bs, tmp32, q);
     launch_block_syms_b(P->ids, P->starts, P->rstart, R, P->seg_dev, ntot, P->v_id, P->v_cnt, q);
-    launch_slot_syms_b(P->seg_dev, pre_256, L.blocks_256, P->tune.slot_grid, R, F, perm, keys,
+    launch_slot_syms_b(P->seg_dev, pre_256, L.blocks_256, P->tune.slot_grid, R, F, P->D, perm, keys,
                        P->slot_rec, ntot, v_rel, v_sup, q_slot, q);
     enc_enqueue(P, EL, out, cap, false, q);
     if (perm_copy) launch_copy_perm_b(perm, P->seg_dev, pre_tile, ts, R, P->permdst_dev, q);
@@ -1274,6 +1279,7 @@ lcp_status run_t(lcp_plan_s* P, const lcp_frame_in* fr, int D, const RunFrame* r
 struct ParsedHdr {
   int mode, F, k, cl, A;
   int scale;  // temporal records: residual step (Sec. 7.4.2); 1 for spatial ones
+  int dims;   // spatial records: spatial dimensions (byte 52; 3 for temporal ones)
   uint64_t n, B, total, seq, ref_seq;
   uint32_t bn[3];
   float m[kMaxF], eb_q[kMaxF];
@@ -1303,7 +1309,10 @@ lcp_status parse_header(const uint8_t* b, uint64_t size, ParsedHdr* h) {
   h->A = b[10];
   h->scale = b[11] ? b[11] : 1;
   if ((h->mode == 0 && b[11] != 0) || h->scale > 15 || h->scale % 2 == 0) return LCP_ERR_CORRUPT;
-  if (h->mode > 1 || h->F < 3 || h->F > kMaxF || h->k > 16 || h->cl < 5 || h->cl > 16)
+  h->dims = b[52] ? b[52] : 3;
+  if (b[52] > 2 || (h->mode == 1 && b[52] != 0)) return LCP_ERR_CORRUPT;
+  if (h->mode > 1 || h->F < (h->mode == 0 ? h->dims : 1) || h->F > kMaxF || h->k > 16 ||
+      h->cl < 5 || h->cl > 16)
     return LCP_ERR_CORRUPT;
   int A = h->mode == 0 ? h->F + 2 : h->F;
   uint64_t hdr = (uint64_t)kHdrBytes + 8ull * h->F + (uint64_t)kDirBytes * A;
@@ -1419,6 +1428,8 @@ lcp_status decompress_s_batch(lcp_plan_s* P, const ParsedHdr* H, const lcp_blob*
     g.bn0 = h.bn[0];
     g.bn1 = h.bn[1];
     g.k = h.k;
+    g.D = h.dims;
+    if (h.dims != H[0].dims) return LCP_ERR_ARG;  // one batch, one dimensionality
     ps[r] = bs;
     pb[r] = bb;
     bs += (uint32_t)((h.n + kSeg1k - 1) / kSeg1k);
@@ -1453,7 +1464,7 @@ lcp_status decompress_s_batch(lcp_plan_s* P, const ParsedHdr* H, const lcp_blob*
         const int f = a - 2;
         d.out = P->v_slot + (uint64_t)f * ntot + g.off;
         d.mode = 2;
-        d.limit = f < 3 ? (1ull << h.k) : (uint64_t)kQLimit;
+        d.limit = f < h.dims ? (1ull << h.k) : (uint64_t)kQLimit;
       }
       bytes += h.anb[a] + (a < 2 ? 8 : 4) * h.an[a];
     }
@@ -1481,9 +1492,10 @@ lcp_status decompress_s_batch(lcp_plan_s* P, const ParsedHdr* H, const lcp_blob*
   launch_s_blocks_b(ids, cnt, cum, P->dseg_dev, pre_blk, bb, R, Btot, ntot, P->corner, P->flags,
                     P->err, s);
   uint32_t* tmp32 = reinterpret_cast<uint32_t*>(P->scan_tmp);
+  const int D = H[0].dims;
   uint32_t* arrs[4] = {P->flags, P->v_slot, P->v_slot + ntot, P->v_slot + 2 * ntot};
-  scan_device4(arrs, 4, ntot, tmp32, s);
-  seg_rebase<uint32_t>(P->v_slot, ntot, 3, P->dseg_dev, pre_slot, bs, R, false,
+  scan_device4(arrs, 1 + D, ntot, tmp32, s);
+  seg_rebase<uint32_t>(P->v_slot, ntot, D, P->dseg_dev, pre_slot, bs, R, false,
                        reinterpret_cast<uint32_t*>(P->segbase), s);
   launch_s_recon_b(P->flags, P->corner, P->v_slot, P->dseg_dev, pre_slot, bs, R, F, Btot, ntot,
                    P->err, s);
@@ -1601,7 +1613,7 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
         d.out = P->dres8 + ((uint64_t)tslot * F + f) * P->N;
         d.esc = reinterpret_cast<int32_t*>(outs[j].fields[f]);
       }
-      d.limit = h.mode == 0 ? (f < 3 ? (1ull << h.k) : (uint64_t)kQLimit) : (1ull << 25);
+      d.limit = h.mode == 0 ? (f < h.dims ? (1ull << h.k) : (uint64_t)kQLimit) : (1ull << 25);
       if (bytes) *bytes += h.anb[a] + 4 * h.an[a];
     }
   };
@@ -1677,11 +1689,10 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
         launch_s_blocks(ids, cnt, cum, B, n, total_blocks, h.bn, h.k, P->corner, P->flags,
                         P->err, s);
         uint32_t* tmp32 = reinterpret_cast<uint32_t*>(P->scan_tmp);
-        uint32_t* arrs[4] = {P->flags, reinterpret_cast<uint32_t*>(outs[j].fields[0]),
-                             reinterpret_cast<uint32_t*>(outs[j].fields[1]),
-                             reinterpret_cast<uint32_t*>(outs[j].fields[2])};
-        scan_device4(arrs, 4, n, tmp32, s);
-        launch_s_recon(P->flags, P->corner, B, F, n, h.k, gd, op, q_slot, P->err, s);
+        uint32_t* arrs[4] = {P->flags, nullptr, nullptr, nullptr};
+        for (int d = 0; d < h.dims; d++) arrs[1 + d] = reinterpret_cast<uint32_t*>(outs[j].fields[d]);
+        scan_device4(arrs, 1 + h.dims, n, tmp32, s);
+        launch_s_recon(P->flags, P->corner, B, F, h.dims, n, h.k, gd, op, q_slot, P->err, s);
       } else {
         const bool extend = chain_len > 0 && chain_len < kChainMax && j > g0 &&
                             chain_last == j - 1 && refq[j] == dq[j - 1] && H[j - 1].n == n &&
@@ -1784,7 +1795,7 @@ void layout_scratch(lcp_plan_s* P, Layout& D, Layout& H) {
   D.add(&P->ids, NS);
   D.add(&P->v_id, NS);
   D.add(&P->v_cnt, NS);
-  D.add(&P->slot_rec, NS * (uint64_t)slot_rec_words(F));
+  D.add(&P->slot_rec, NS * (uint64_t)slot_rec_words(F, P->D));
   D.add(&P->vals0, NS);
   D.add(&P->vals1, NS);
   D.add(&P->hist, sb ? 0 : 256 * ntiles);
@@ -2103,7 +2114,8 @@ lcp_status compress_independent(lcp_plan_s* plan, uint64_t n_frames, const lcp_f
 namespace {
 lcp_status plan_check(const lcp_params& p, const float* const* sample_fields, uint64_t sample_n) {
   const int cl = p.chunk_log2 == 0 ? 10 : p.chunk_log2;
-  if (p.n_fields < 3 || p.n_fields > LCP_MAX_FIELDS || cl < 5 || cl > 12 || p.batch_size < 0 ||
+  if (p.n_fields < 1 || p.n_fields > LCP_MAX_FIELDS || cl < 5 || cl > 12 || p.batch_size < 0 ||
+      p.n_dims < 0 || p.n_dims > 3 || p.n_fields < (p.n_dims ? p.n_dims : 3) ||
       p.block_log2 < -1 || p.block_log2 > 16 || p.max_particles == 0 ||
       p.max_particles > (1ull << 31) || !(p.eb > 0) || p.eb_mode < 0 || p.eb_mode > 2 ||
       p.max_batch_frames < 0 || p.max_batch_frames > kMaxBatch ||
@@ -2123,6 +2135,7 @@ void plan_fill(lcp_plan_s* P, const lcp_params& p) {
   P->p.chunk_log2 = cl;
   P->chunk_log2 = cl;
   P->F = p.n_fields;
+  P->D = p.n_dims ? p.n_dims : 3;
   P->N = p.max_particles;
   if (p.multi_frame) {
     P->RB = 1;

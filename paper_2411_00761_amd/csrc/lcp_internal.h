@@ -63,6 +63,7 @@ struct ArrWork {
 struct RecHdr {
   int mode, F, k, chunk_log2, A;
   int scale;  // temporal records: residual step (byte 11; 1 is written as 0)
+  int dims;   // spatial records: spatial dimensions (byte 52; 3 is written as 0)
   uint64_t n, seq, ref_seq;
   uint32_t bn[3];
   float m[kMaxF], eb_q[kMaxF];
@@ -104,8 +105,8 @@ struct SegDev {
   float m[kMaxF], eb_q[kMaxF];
   double inv[kMaxF];
   uint64_t n, off;
-  uint64_t bn0, bn1;  // Eq. 6 block grid
-  int k, pad;
+  uint64_t bn0, bn1;  // Eq. 6 block grid (1 along axes the data does not have)
+  int k, D;           // block size log2, spatial dimensions (fields 0..D-1)
 };
 // One frame of a spatial decode batch (device table): frame r owns slots
 // [off, off + n) and blocks [boff, boff + B) of the batch-wide arrays.
@@ -114,7 +115,7 @@ struct DSegDev {
   float m[kMaxF], eb_q[kMaxF];
   uint64_t n, off, B, boff, total_blocks;
   uint64_t bn0, bn1;
-  int k, pad;
+  int k, D;  // block size log2, spatial dimensions
 };
 constexpr int kMaxBatch = 1024;       // frames per spatial batch
 constexpr uint32_t kSegExtCap = 256;  // extent workgroups per frame (at most)
@@ -217,10 +218,10 @@ void plan_unbind(lcp_plan_s* P);
 // ceil(n / kSeg256) and ceil(n / kSortTile).  ext receives R x 2F sortable keys (min, max per field).
 void launch_extent_b(const SegDev* S, const uint32_t* pre_ext, uint32_t ext_blocks, int R, int F,
                      uint32_t* ext, uint32_t* part, uint32_t* err, uint64_t bytes, hipStream_t s);
-// rec receives, per particle in input order, a record of slot_rec_words(F)
-// words: its three in-block offsets (16 bits apart) and its supplementary
-// fields' codes.
-int slot_rec_words(int F);
+// rec receives, per particle in input order, a record of slot_rec_words(F, D)
+// words: its D in-block offsets (16 bits apart; word 0 for up to two axes,
+// words 0-1 for three) and its supplementary fields' codes after them.
+int slot_rec_words(int F, int D);
 // The element-wise encode kernels of a batch walk `tiles` tiles of `tile`
 // slots (a multiple of 256; the prefix tables count tiles per frame) with a
 // persistent grid of `grid` workgroups (0: one workgroup per tile).  Launch
@@ -229,7 +230,7 @@ struct TileShape {
   uint32_t tile, tiles, grid;
 };
 void launch_quant_key_b(const SegDev* S, const uint32_t* pre_tile, const TileShape& ts, int R,
-                        int F, uint64_t* keys, uint32_t* vals, uint32_t* rec, uint64_t ntot,
+                        int F, int D, uint64_t* keys, uint32_t* vals, uint32_t* rec, uint64_t ntot,
                         hipStream_t s);
 // Non-empty blocks of every frame: ids, global start slots,
 // rstart[r] (first block of frame r; rstart[R] = all blocks) and Bs[r].
@@ -244,7 +245,7 @@ void launch_block_syms_b(const uint64_t* ids, const uint32_t* starts, const uint
 // v_rel: [3][ntot], v_sup: [F-3][ntot]; q_slot (nullable): [F][ntot]; keys:
 // the sorted block keys (slot order).
 void launch_slot_syms_b(const SegDev* S, const uint32_t* pre_256, uint32_t tiles, uint32_t grid,
-                        int R, int F, const uint32_t* perm, const uint64_t* keys,
+                        int R, int F, int D, const uint32_t* perm, const uint64_t* keys,
                         const uint32_t* rec, uint64_t ntot, uint32_t* v_rel, uint32_t* v_sup,
                         int32_t* q_slot, hipStream_t s);
 // dst[r] (device table of device pointers, entries may be null) <- perm slice of frame r.
@@ -346,7 +347,7 @@ void launch_s_blocks(const uint64_t* ids, const uint64_t* cnt, uint64_t* cum, ui
 // Reconstruction in place: out.p[f] holds the decoded u32 symbols (scanned
 // relative positions for f < 3, codes for supplementary fields) and receives
 // the float32 values.
-void launch_s_recon(const uint32_t* blk, const uint32_t* corner, uint64_t B, int F, uint64_t n,
+void launch_s_recon(const uint32_t* blk, const uint32_t* corner, uint64_t B, int F, int D, uint64_t n,
                     int k, const GridDev& g, const OutPtrs& out, int32_t* q_slot, uint32_t* err,
                     hipStream_t s);
 // The codes the last of J temporal frames leaves as the next reference: with

@@ -47,7 +47,7 @@ class lcp_params(C.Structure):
                 ("chunk_log2", C.c_int), ("max_particles", C.c_uint64),
                 ("hbm_budget_bytes", C.c_uint64), ("device", C.c_int),
                 ("max_batch_particles", C.c_uint64), ("max_batch_frames", C.c_int),
-                ("anchor_scale", C.c_int)]
+                ("anchor_scale", C.c_int), ("n_dims", C.c_int)]
 
 
 class lcp_tuning(C.Structure):
@@ -209,13 +209,13 @@ class Plan:
                  multi_frame: bool = False, batch_size: int = 16, block_log2: int = -1,
                  chunk_log2: int = 10, max_particles: int = 1 << 20, hbm_budget_bytes: int = 0,
                  device: int = 0, sample=None, max_batch_particles: int = 0,
-                 max_batch_frames: int = 0, anchor_scale: int = 0):
+                 max_batch_frames: int = 0, anchor_scale: int = 0, n_dims: int = 0):
         import torch
         self.F = n_fields
         self.device = device
         self.params = lcp_params(eb_mode, eb, n_fields, int(multi_frame), batch_size, block_log2,
                                  chunk_log2, max_particles, hbm_budget_bytes, device,
-                                 max_batch_particles, max_batch_frames, anchor_scale)
+                                 max_batch_particles, max_batch_frames, anchor_scale, n_dims)
         ptrs = None
         sn = 0
         if sample is not None:
@@ -417,9 +417,9 @@ class Server:
 
     def open_stream(self, eb: float, eb_mode: int = EB_ABS, n_fields: int = 3, batch_size: int = 16,
                     block_log2: int = -1, chunk_log2: int = 10, max_particles: int = 1 << 20,
-                    sample=None, anchor_scale: int = 0) -> int:
+                    sample=None, anchor_scale: int = 0, n_dims: int = 0) -> int:
         params = lcp_params(eb_mode, eb, n_fields, 1, batch_size, block_log2, chunk_log2,
-                            max_particles, 0, self.device, 0, 0, anchor_scale)
+                            max_particles, 0, self.device, 0, 0, anchor_scale, n_dims)
         ptrs, sn = None, 0
         if sample is not None:
             sample = sample.contiguous()
