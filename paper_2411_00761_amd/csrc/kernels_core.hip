@@ -46,7 +46,10 @@ constexpr int kRsItems = 16;
 constexpr int kRsTile = kThreads * kRsItems;  // 4096 keys per tile
 static_assert(kRsTile == (int)kSortTile, "sort tile");
 
-__global__ __launch_bounds__(kThreads) void k_radix_hist(const uint64_t* keys, const SegDev* S,
+// K: the key type, u32 when the block ids fit 32 bits (half the sort's key
+// traffic), else u64.
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_radix_hist(const K* keys, const SegDev* S,
                                                          const uint32_t* pre, int R, int shift,
                                                          uint32_t* hist) {
   __shared__ uint32_t cnt[kThreads / kWave][256];
@@ -66,13 +69,14 @@ __global__ __launch_bounds__(kThreads) void k_radix_hist(const uint64_t* keys, c
   hist[(uint64_t)pre[r] * 256 + (uint64_t)t * nt + lt] = cnt[0][t] + cnt[1][t] + cnt[2][t] + cnt[3][t];
 }
 
-__global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* kin,
-                                                            const uint32_t* vin, uint64_t* kout,
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_radix_scatter(const K* kin,
+                                                            const uint32_t* vin, K* kout,
                                                             uint32_t* vout, const SegDev* S,
                                                             const uint32_t* pre, int R, int shift,
                                                             const uint32_t* offs,
                                                             uint64_t entries, uint64_t ntot) {
-  __shared__ uint64_t sk[kRsTile];
+  __shared__ K sk[kRsTile];
   __shared__ uint32_t sv[kRsTile];
   __shared__ uint32_t gbase[256], lstart[256], run[256];
   __shared__ uint32_t wcnt[kThreads / kWave][256];
@@ -97,7 +101,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* kin,
   for (int rd = 0; rd < kRsItems; rd++) {
     const uint32_t li = (uint32_t)rd * kThreads + t;
     const bool valid = li < cnt;
-    const uint64_t key = valid ? kin[tile0 + li] : 0;
+    const K key = valid ? kin[tile0 + li] : (K)0;
     const uint32_t val = valid ? vin[tile0 + li] : 0;
     const uint32_t d = (uint32_t)(key >> shift) & 255u;
 #pragma unroll
@@ -128,7 +132,7 @@ __global__ __launch_bounds__(kThreads) void k_radix_scatter(const uint64_t* kin,
   // the tile in digit order: consecutive slots of one digit go to consecutive
   // output positions
   for (uint32_t i = t; i < cnt; i += kThreads) {
-    const uint64_t key = sk[i];
+    const K key = sk[i];
     const uint32_t d = (uint32_t)(key >> shift) & 255u;
     const uint64_t pos = (uint64_t)gbase[d] + (i - lstart[d]);
     kout[pos] = key;
@@ -780,9 +784,10 @@ __global__ __launch_bounds__(kThreads) void k_extent_final_b(const uint32_t* par
 // slot instead of separate values.
 // Persistent over the batch's tiles of `tile` slots (tile t of frame r at
 // prefix pre[r]); every element-wise batch kernel below walks its tiles so.
+template <typename K>
 __global__ __launch_bounds__(kThreads) void k_quant_key_b(const SegDev* S, const uint32_t* pre,
                                                           int R, int F, uint32_t tile,
-                                                          uint32_t tiles, uint64_t* keys,
+                                                          uint32_t tiles, K* keys,
                                                           uint32_t* vals, uint32_t* rec, int rw) {
   for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
   const int r = seg_of_block(pre, R, t);
@@ -799,7 +804,7 @@ __global__ __launch_bounds__(kThreads) void k_quant_key_b(const SegDev* S, const
       const uint64_t q1 = D > 1 ? (uint64_t)quantise(g.x[1][i], g.m[1], g.inv[1]) : 0;
       const uint64_t q2 = D > 2 ? (uint64_t)quantise(g.x[2][i], g.m[2], g.inv[2]) : 0;
       const uint64_t b0 = q0 >> k, b1 = q1 >> k, b2 = q2 >> k;
-      keys[g.off + i] = b0 + g.bn0 * (b1 + g.bn1 * b2);  // Eq. 6, x fastest
+      keys[g.off + i] = (K)(b0 + g.bn0 * (b1 + g.bn1 * b2));  // Eq. 6, x fastest
       vals[g.off + i] = (uint32_t)i;
       const uint64_t pr = (q0 & pm) | ((q1 & pm) << 16) | ((q2 & pm) << 32);
       uint32_t w[8] = {(uint32_t)pr, (uint32_t)(pr >> 32), 0, 0, 0, 0, 0, 0};
@@ -828,7 +833,8 @@ __global__ __launch_bounds__(kThreads) void k_quant_key_b(const SegDev* S, const
 
 // A slot starts a non-empty block when it is its frame's first slot or its key
 // differs from the previous slot's.
-__global__ __launch_bounds__(kThreads) void k_run_flags_b(const uint64_t* keys, const SegDev* S,
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_run_flags_b(const K* keys, const SegDev* S,
                                                           const uint32_t* pre, int R,
                                                           uint32_t tile, uint32_t tiles,
                                                           uint32_t* flags) {
@@ -843,7 +849,8 @@ __global__ __launch_bounds__(kThreads) void k_run_flags_b(const uint64_t* keys, 
   }
 }
 
-__global__ __launch_bounds__(kThreads) void k_runs_write_b(const uint64_t* keys,
+template <typename K>
+__global__ __launch_bounds__(kThreads) void k_runs_write_b(const K* keys,
                                                            const uint32_t* scan, const SegDev* S,
                                                            const uint32_t* pre, int R,
                                                            uint32_t tile, uint32_t tiles,
@@ -928,9 +935,10 @@ __device__ inline void load_rec(const uint32_t* rec, uint64_t i, int rw, uint32_
   }
 }
 
+template <typename K>
 __global__ __launch_bounds__(kThreads) void k_slot_syms_b(const SegDev* S, const uint32_t* pre,
                                                           int R, int F, const uint32_t* perm,
-                                                          const uint64_t* keys,
+                                                          const K* keys,
                                                           const uint32_t* rec, int rw,
                                                           uint64_t ntot, uint32_t* v_rel,
                                                           uint32_t* v_sup, int32_t* q_slot,
@@ -963,7 +971,7 @@ __global__ __launch_bounds__(kThreads) void k_slot_syms_b(const SegDev* S, const
     for (int j = 0; j < kMaxF - 1; j++)
       if (D + j < F) v_sup[(uint64_t)j * ntot + off + s] = sup[j];
     if (q_slot) {
-      const uint64_t key = keys[off + s];
+      const uint64_t key = (uint64_t)keys[off + s];
       const uint64_t bx = key % g.bn0, rest = key / g.bn0;
       const uint64_t b3[3] = {bx, rest % g.bn1, rest / g.bn1};
       for (int d = 0; d < D; d++)
@@ -1402,22 +1410,35 @@ inline uint32_t persistent_grid(uint32_t tiles, uint32_t grid) {
 
 void launch_quant_key_b(const SegDev* S, const uint32_t* pre_tile, const TileShape& ts, int R,
                         int F, int D, uint64_t* keys, uint32_t* vals, uint32_t* rec, uint64_t ntot,
-                        hipStream_t s) {
+                        bool key32, hipStream_t s) {
   const int rw = slot_rec_words(F, D);
-  launch_timed("quant_key", ntot * (4ull * F + 12 + 4ull * rw), k_quant_key_b,
-               persistent_grid(ts.tiles, ts.grid), kThreads, 0, s, S, pre_tile, R, F, ts.tile,
-               ts.tiles, keys, vals, rec, rw);
+  const uint64_t bytes = ntot * (4ull * F + (key32 ? 8 : 12) + 4ull * rw);
+  const uint32_t g = persistent_grid(ts.tiles, ts.grid);
+  if (key32)
+    launch_timed("quant_key", bytes, k_quant_key_b<uint32_t>, g, kThreads, 0, s, S, pre_tile, R,
+                 F, ts.tile, ts.tiles, reinterpret_cast<uint32_t*>(keys), vals, rec, rw);
+  else
+    launch_timed("quant_key", bytes, k_quant_key_b<uint64_t>, g, kThreads, 0, s, S, pre_tile, R,
+                 F, ts.tile, ts.tiles, keys, vals, rec, rw);
 }
 
 void launch_runs_b(const uint64_t* keys, const SegDev* S, const uint32_t* pre_tile,
                    const TileShape& ts, int R, uint64_t ntot, uint32_t* flags_scan, uint64_t* ids,
                    uint32_t* starts, uint32_t* rstart, uint32_t* Bs, uint32_t* tmp32,
-                   hipStream_t s) {
+                   bool key32, hipStream_t s) {
   const uint32_t g = persistent_grid(ts.tiles, ts.grid);
-  k_run_flags_b<<<g, kThreads, 0, s>>>(keys, S, pre_tile, R, ts.tile, ts.tiles, flags_scan);
+  const uint32_t* k32 = reinterpret_cast<const uint32_t*>(keys);
+  if (key32)
+    k_run_flags_b<uint32_t><<<g, kThreads, 0, s>>>(k32, S, pre_tile, R, ts.tile, ts.tiles, flags_scan);
+  else
+    k_run_flags_b<uint64_t><<<g, kThreads, 0, s>>>(keys, S, pre_tile, R, ts.tile, ts.tiles, flags_scan);
   scan_device<uint32_t>(flags_scan, ntot, nullptr, false, tmp32, s);
-  k_runs_write_b<<<g, kThreads, 0, s>>>(keys, flags_scan, S, pre_tile, R, ts.tile, ts.tiles, ids,
-                                        starts, rstart, Bs);
+  if (key32)
+    k_runs_write_b<uint32_t><<<g, kThreads, 0, s>>>(k32, flags_scan, S, pre_tile, R, ts.tile,
+                                                    ts.tiles, ids, starts, rstart, Bs);
+  else
+    k_runs_write_b<uint64_t><<<g, kThreads, 0, s>>>(keys, flags_scan, S, pre_tile, R, ts.tile,
+                                                    ts.tiles, ids, starts, rstart, Bs);
 }
 
 void launch_block_syms_b(const uint64_t* ids, const uint32_t* starts, const uint32_t* rstart,
@@ -1430,11 +1451,17 @@ void launch_block_syms_b(const uint64_t* ids, const uint32_t* starts, const uint
 void launch_slot_syms_b(const SegDev* S, const uint32_t* pre_256, uint32_t tiles, uint32_t grid,
                         int R, int F, int D, const uint32_t* perm, const uint64_t* keys,
                         const uint32_t* rec, uint64_t ntot, uint32_t* v_rel, uint32_t* v_sup,
-                        int32_t* q_slot, hipStream_t s) {
+                        int32_t* q_slot, bool key32, hipStream_t s) {
   const int rw = slot_rec_words(F, D);
-  uint64_t bytes = ntot * (4 + 4ull * rw + 4ull * F + (q_slot ? 8 + 4ull * F : 0));
-  launch_timed("slot_syms", bytes, k_slot_syms_b, persistent_grid(tiles, grid), kThreads, 0, s,
-               S, pre_256, R, F, perm, keys, rec, rw, ntot, v_rel, v_sup, q_slot, tiles);
+  uint64_t bytes = ntot * (4 + 4ull * rw + 4ull * F + (q_slot ? (key32 ? 4 : 8) + 4ull * F : 0));
+  const uint32_t g = persistent_grid(tiles, grid);
+  if (key32)
+    launch_timed("slot_syms", bytes, k_slot_syms_b<uint32_t>, g, kThreads, 0, s, S, pre_256, R, F,
+                 perm, reinterpret_cast<const uint32_t*>(keys), rec, rw, ntot, v_rel, v_sup,
+                 q_slot, tiles);
+  else
+    launch_timed("slot_syms", bytes, k_slot_syms_b<uint64_t>, g, kThreads, 0, s, S, pre_256, R, F,
+                 perm, keys, rec, rw, ntot, v_rel, v_sup, q_slot, tiles);
 }
 
 void launch_copy_perm_b(const uint32_t* perm, const SegDev* S, const uint32_t* pre_tile,
@@ -1445,23 +1472,34 @@ void launch_copy_perm_b(const uint32_t* perm, const SegDev* S, const uint32_t* p
 
 int radix_result(int bits) { return ((bits + 7) / 8) & 1; }
 
-int radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, const SegDev* S,
-               const uint32_t* pre_tile, uint32_t ntiles, int R, uint64_t ntot, int bits,
-               uint32_t* hist, uint32_t* tmp32, hipStream_t s) {
+template <typename K>
+int radix_sort_k(K* k0, uint32_t* v0, K* k1, uint32_t* v1, const SegDev* S,
+                 const uint32_t* pre_tile, uint32_t ntiles, int R, uint64_t ntot, int bits,
+                 uint32_t* hist, uint32_t* tmp32, hipStream_t s) {
   const uint64_t entries = (uint64_t)ntiles * 256;
   int cur = 0;
   for (int shift = 0; shift < bits; shift += 8) {
-    uint64_t* kin = cur ? k1 : k0;
+    K* kin = cur ? k1 : k0;
     uint32_t* vin = cur ? v1 : v0;
-    uint64_t* kout = cur ? k0 : k1;
+    K* kout = cur ? k0 : k1;
     uint32_t* vout = cur ? v0 : v1;
-    k_radix_hist<<<ntiles, kThreads, 0, s>>>(kin, S, pre_tile, R, shift, hist);
+    k_radix_hist<K><<<ntiles, kThreads, 0, s>>>(kin, S, pre_tile, R, shift, hist);
     scan_device<uint32_t>(hist, entries, nullptr, true, tmp32, s);
-    launch_timed("radix_scatter", ntot * 24, k_radix_scatter, ntiles, kThreads, 0, s,
-               kin, vin, kout, vout, S, pre_tile, R, shift, hist, entries, ntot);
+    launch_timed("radix_scatter", ntot * (2 * sizeof(K) + 8), k_radix_scatter<K>, ntiles, kThreads,
+                 0, s, kin, vin, kout, vout, S, pre_tile, R, shift, hist, entries, ntot);
     cur ^= 1;
   }
   return cur;
+}
+
+int radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, const SegDev* S,
+               const uint32_t* pre_tile, uint32_t ntiles, int R, uint64_t ntot, int bits,
+               uint32_t* hist, uint32_t* tmp32, bool key32, hipStream_t s) {
+  if (key32)
+    return radix_sort_k<uint32_t>(reinterpret_cast<uint32_t*>(k0), v0,
+                                  reinterpret_cast<uint32_t*>(k1), v1, S, pre_tile, ntiles, R, ntot,
+                                  bits, hist, tmp32, s);
+  return radix_sort_k<uint64_t>(k0, v0, k1, v1, S, pre_tile, ntiles, R, ntot, bits, hist, tmp32, s);
 }
 
 size_t scan_tmp_elems(uint64_t n) {

@@ -735,17 +735,18 @@ lcp_status compress_s_batch(lcp_plan_s* P, int R, const HostGrid (*g)[kMaxF],
   const uint32_t* pre_tile = P->segpre_dev + (R + 1);
   const uint32_t* pre_256 = P->segpre_dev + 2 * (R + 1);
   const TileShape ts{P->tune.tile, L.blocks_1k, P->tune.grid};
+  const bool key32 = sort_bits <= 32;  // every block id fits 32 bits
   auto kernels = [&](hipStream_t q) {
     launch_quant_key_b(P->seg_dev, pre_tile, ts, R, F, P->D, P->keys0, P->vals0, P->slot_rec,
-                       ntot, q);
+                       ntot, key32, q);
     uint32_t* tmp32 = reinterpret_cast<uint32_t*>(P->scan_tmp);
     radix_sort(P->keys0, P->vals0, P->keys1, P->vals1, P->seg_dev, P->segpre_dev + 3 * (R + 1),
-               L.tiles, R, ntot, sort_bits, P->hist, tmp32, q);
+               L.tiles, R, ntot, sort_bits, P->hist, tmp32, key32, q);
     launch_runs_b(keys, P->seg_dev, pre_tile, ts, R, ntot, P->flags, P->ids, P->starts, P->rstart,
-                  P->Bs, tmp32, q);
+                  P->Bs, tmp32, key32, q);
     launch_block_syms_b(P->ids, P->starts, P->rstart, R, P->seg_dev, ntot, P->v_id, P->v_cnt, q);
     launch_slot_syms_b(P->seg_dev, pre_256, L.blocks_256, P->tune.slot_grid, R, F, P->D, perm, keys,
-                       P->slot_rec, ntot, v_rel, v_sup, q_slot, q);
+                       P->slot_rec, ntot, v_rel, v_sup, q_slot, key32, q);
     enc_enqueue(P, EL, out, cap, false, q);
     if (perm_copy) launch_copy_perm_b(perm, P->seg_dev, pre_tile, ts, R, P->permdst_dev, q);
   };

@@ -231,13 +231,13 @@ struct TileShape {
 };
 void launch_quant_key_b(const SegDev* S, const uint32_t* pre_tile, const TileShape& ts, int R,
                         int F, int D, uint64_t* keys, uint32_t* vals, uint32_t* rec, uint64_t ntot,
-                        hipStream_t s);
+                        bool key32, hipStream_t s);
 // Non-empty blocks of every frame: ids, global start slots,
 // rstart[r] (first block of frame r; rstart[R] = all blocks) and Bs[r].
 void launch_runs_b(const uint64_t* keys, const SegDev* S, const uint32_t* pre_tile,
                    const TileShape& ts, int R, uint64_t ntot, uint32_t* flags_scan, uint64_t* ids,
                    uint32_t* starts, uint32_t* rstart, uint32_t* Bs, uint32_t* tmp32,
-                   hipStream_t s);
+                   bool key32, hipStream_t s);
 // Block symbols of frame r go to v_id / v_cnt + S[r].off.
 void launch_block_syms_b(const uint64_t* ids, const uint32_t* starts, const uint32_t* rstart,
                          int R, const SegDev* S, uint64_t ntot, uint64_t* v_id, uint64_t* v_cnt,
@@ -247,11 +247,12 @@ void launch_block_syms_b(const uint64_t* ids, const uint32_t* starts, const uint
 void launch_slot_syms_b(const SegDev* S, const uint32_t* pre_256, uint32_t tiles, uint32_t grid,
                         int R, int F, int D, const uint32_t* perm, const uint64_t* keys,
                         const uint32_t* rec, uint64_t ntot, uint32_t* v_rel, uint32_t* v_sup,
-                        int32_t* q_slot, hipStream_t s);
+                        int32_t* q_slot, bool key32, hipStream_t s);
 // dst[r] (device table of device pointers, entries may be null) <- perm slice of frame r.
 void launch_copy_perm_b(const uint32_t* perm, const SegDev* S, const uint32_t* pre_tile,
                         const TileShape& ts, int R, uint32_t* const* dst, hipStream_t s);
 
+// Keys are u32 (key32: every block id below 2^32) or u64 in the same buffers.
 // Stable LSD radix sort of (key, value) by the low `bits` key bits, within
 // each frame of the SegDev table (pre_tile: ceil(n / kSortTile) tiles per
 // frame, ntiles in all; hist: 256 * ntiles u32).  Returns the buffer index
@@ -261,7 +262,7 @@ constexpr uint32_t kSortTile = 4096;
 int radix_result(int bits);
 int radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1, const SegDev* S,
                const uint32_t* pre_tile, uint32_t ntiles, int R, uint64_t ntot, int bits,
-               uint32_t* hist, uint32_t* tmp32, hipStream_t s);
+               uint32_t* hist, uint32_t* tmp32, bool key32, hipStream_t s);
 template <typename T>
 void scan_device(T* data, uint64_t n, const uint32_t* n_dev, bool exclusive, T* tmp,
                  hipStream_t s);
