@@ -313,10 +313,21 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
     for (uint64_t s4 = gid; s4 < n / 4; s4 += stride) {
       const uint4 iv = reinterpret_cast<const uint4*>(perm_ref)[s4];
       const uint32_t idx[4] = {iv.x, iv.y, iv.z, iv.w};
+      // consecutive inputs from a multiple of four: one 16-byte load per field
+      const bool seq4 = (idx[0] & 3u) == 0 && idx[1] == idx[0] + 1 && idx[2] == idx[0] + 2 &&
+                        idx[3] == idx[0] + 3;
       for (int f = 0; f < F; f++) {
         float xv[4];
+        if (seq4 && ((uintptr_t)x.p[f] & 15) == 0) {
+          const float4 v4 = *reinterpret_cast<const float4*>(x.p[f] + idx[0]);
+          xv[0] = v4.x;
+          xv[1] = v4.y;
+          xv[2] = v4.z;
+          xv[3] = v4.w;
+        } else {
 #pragma unroll
-        for (int j = 0; j < 4; j++) xv[j] = x.p[f][idx[j]];
+          for (int j = 0; j < 4; j++) xv[j] = x.p[f][idx[j]];
+        }
         const int4 qr = reinterpret_cast<const int4*>(q_ref + (uint64_t)f * n)[s4];
         const int32_t qrv[4] = {qr.x, qr.y, qr.z, qr.w};
         uint32_t rv[4];
@@ -443,6 +454,11 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
       idx[0] = perm[gid];
     }
   }
+  // four slots whose inputs are four consecutive values from a multiple of
+  // four (a slot order that keeps runs of the input order, as a trajectory's
+  // does) are read with one 16-byte load per field instead of four gathers
+  const bool seq4 = vec && mine && (idx[0] & 3u) == 0 && idx[1] == idx[0] + 1 &&
+                    idx[2] == idx[0] + 2 && idx[3] == idx[0] + 3;
 #pragma unroll
   for (int f = 0; f < F; f++) {
     q[f][0] = q[f][1] = q[f][2] = q[f][3] = 0;
@@ -458,9 +474,35 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
       }
     }
   }
+  // vector path: the next frame's values are requested while this frame is
+  // coded (software pipelining: twice the loads in flight per wave)
+  float xn[F][4];
+  auto load_frame = [&](int j) {
+#pragma unroll
+    for (int f = 0; f < F; f++) {
+      const float* x = fr.x[j][f];
+      if (seq4 && ((uintptr_t)x & 15) == 0) {
+        const float4 v4 = *reinterpret_cast<const float4*>(x + idx[0]);
+        xn[f][0] = v4.x;
+        xn[f][1] = v4.y;
+        xn[f][2] = v4.z;
+        xn[f][3] = v4.w;
+      } else if (mine) {
+#pragma unroll
+        for (int u = 0; u < 4; u++) xn[f][u] = x[idx[u]];
+      }
+    }
+  };
+  if (vec) load_frame(0);
   __syncthreads();
   for (int j = 0; j < J; j++) {
     uint32_t bad = 0;
+    float xc[F][4];
+#pragma unroll
+    for (int f = 0; f < F; f++)
+#pragma unroll
+      for (int u = 0; u < 4; u++) xc[f][u] = xn[f][u];
+    if (vec && j + 1 < J) load_frame(j + 1);
 #pragma unroll
     for (int f = 0; f < F; f++) {
       const uint64_t a = (uint64_t)(a0 + j) * F + f;
@@ -471,11 +513,7 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
       uint32_t* oesc = vesc + a * astride;
       uint32_t rmax = 0;
       if (vec) {
-        float xv[4];
-        if (mine) {
-#pragma unroll
-          for (int u = 0; u < 4; u++) xv[u] = x[idx[u]];
-        }
+        const float* xv = xc[f];
         uint32_t rv[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
@@ -1556,6 +1594,7 @@ template void scan_device<uint64_t>(uint64_t*, uint64_t, const uint32_t*, bool, 
 template <typename T>
 void seg_rebase(T* X, uint64_t stride, int nd, const DSegDev* D, const uint32_t* pre,
                 uint32_t blocks, int R, bool by_block, T* bases, hipStream_t s) {
+  if (R == 1) return;  // a lone frame starts the batch: its base is zero
   k_seg_bases<T><<<dim3((R + kThreads - 1) / kThreads, nd), kThreads, 0, s>>>(X, stride, D, R,
                                                                             by_block, bases);
   k_seg_rebase<T><<<dim3(blocks, nd), kThreads, 0, s>>>(X, stride, D, pre, R, by_block, bases);
