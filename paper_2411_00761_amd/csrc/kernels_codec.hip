@@ -766,6 +766,8 @@ __global__ __launch_bounds__(kHT) void k_huff_build(const EncArr* E, uint32_t* p
 // the arrays for which fewer halvings already fit (the pick below never reads
 // past the first count that fits, so those entries need not be written).
 constexpr int kFirstHalvings = 8;  // candidates built first; the rest only when none fits
+// Below this many candidate workgroups (arrays x 31) all are built in one launch.
+constexpr uint64_t kOneLaunchCandidates = 1024;
 
 __global__ __launch_bounds__(kHT) void k_huff_lengths(const ArrWork* W, uint8_t* lens_all,
                                                       uint32_t* maxd_all, int h0) {
@@ -2537,9 +2539,15 @@ void launch_encode(const EncLaunch& L, int chunk_log2, ArrWork* work, const EncS
     launch_timed("huff_build", 0, k_huff_build, NA, kHT, 0, s, L.arrs, X.hist_part, X.hist_max,
                  work, X.huff_lens, X.huff_maxd, hist_done ? 1 : 0, chunk_log2);
   if (!hist_done) {
-    k_huff_lengths<<<dim3(NA, kFirstHalvings), kHT, 0, s>>>(work, X.huff_lens, X.huff_maxd, 1);
-    k_huff_lengths<<<dim3(NA, kHalvings - 1 - kFirstHalvings), kHT, 0, s>>>(
-        work, X.huff_lens, X.huff_maxd, 1 + kFirstHalvings);
+    if ((uint64_t)NA * (kHalvings - 1) <= kOneLaunchCandidates) {
+      // few arrays: every candidate in one launch (the GPU is far from full
+      // either way, and a second launch would cost its own latency)
+      k_huff_lengths<<<dim3(NA, kHalvings - 1), kHT, 0, s>>>(work, X.huff_lens, X.huff_maxd, 1);
+    } else {
+      k_huff_lengths<<<dim3(NA, kFirstHalvings), kHT, 0, s>>>(work, X.huff_lens, X.huff_maxd, 1);
+      k_huff_lengths<<<dim3(NA, kHalvings - 1 - kFirstHalvings), kHT, 0, s>>>(
+          work, X.huff_lens, X.huff_maxd, 1 + kFirstHalvings);
+    }
     k_huff_codes<<<NA, kHT, 0, s>>>(L.arrs, work, X.huff_lens, X.huff_maxd, chunk_log2);
   }
   const uint32_t slot32 = enc_slot_words(false, chunk_log2), slot64 = enc_slot_words(true, chunk_log2);
