@@ -1437,6 +1437,13 @@ void launch_extent_b(const SegDev* S, const uint32_t* pre_ext, uint32_t ext_bloc
   k_extent_final_b<<<dim3(R, F), kThreads, 0, s>>>(part, pre_ext, R, F, ext_blocks, ext);
 }
 
+// Frames one run launch takes at F fields: its LDS counts (J F kRunPriv words)
+// stay within 48 KiB.
+int run_launch_frames(int F) {
+  const int j = (48 << 10) / (F * kRunPriv * 4);
+  return j < kRunMax ? j : kRunMax;
+}
+
 int slot_rec_words(int F, int D) {
   const int w = (D == 3 ? 2 : 1) + (F - D);  // offsets, then supplementary codes
   return w <= 2 ? 2 : (w <= 4 ? 4 : 8);

@@ -1920,7 +1920,7 @@ lcp_status alloc_state(lcp_plan_s* P) {
 // Frames a temporal run of a multi-frame plan codes at once: as many as keep
 // the run's buffers (residual bytes, escapes, staging, histogram copies) within
 // kRunBytes, at most kRunMax; fewer than two means no runs.
-constexpr uint64_t kRunBytes = 1ull << 30;
+constexpr uint64_t kRunBytes = 2ull << 30;
 int run_frames_for(const lcp_plan_s* P) {
   if (!P->p.multi_frame) return 0;
   const uint64_t N = P->N, F = (uint64_t)P->F;
@@ -1928,7 +1928,7 @@ int run_frames_for(const lcp_plan_s* P) {
   const uint64_t per = F * ((N + 63) & ~63ull) * 5 + F * chunks * 4 * (enc_slot_words(false, P->chunk_log2) + 1) +
                        F * kRunCopies * kAlphabet * 4ull;
   uint64_t d = kRunBytes / per;
-  if (d > (uint64_t)kRunMax) d = kRunMax;
+  if (d > (uint64_t)run_launch_frames(P->F)) d = run_launch_frames(P->F);
   return d < 2 ? 0 : (int)d;
 }
 
