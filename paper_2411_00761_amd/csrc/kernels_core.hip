@@ -581,91 +581,148 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
   }
 }
 
-// Temporal frames of several streams in one launch: workgroup b codes a tile
-// of 256 items (four slots each on a frame's vector path, one otherwise) of the
-// frame the prefix table gives it, exactly as k_t_resid codes a frame, its
-// counts merged into that frame's arrays' spread copies.
+// Temporal frames of several streams in one launch.  The launch's tiles of 256
+// items (four slots each on a frame's vector path, one otherwise), counted
+// frame after frame by the prefix table, are split into contiguous ranges, one
+// per workgroup (a persistent grid of at most kMultiGrid workgroups); a
+// workgroup codes its tiles exactly as k_t_resid codes a frame and keeps the
+// counts of the frame it is in in its LDS bins, merging them into that frame's
+// arrays' spread copies when it moves to the next frame and at the end (so a
+// frame costs one merge per workgroup that touches it, not one per tile).
+constexpr uint32_t kMultiGrid = 2048;
 __global__ __launch_bounds__(kThreads) void k_t_resid_multi(const TFrameDev* T, const uint32_t* pre,
-                                                            int R, int F, uint32_t* hist_part,
+                                                            int R, int F, uint32_t tiles,
+                                                            uint32_t* hist_part,
                                                             unsigned long long* hist_max,
                                                             int copies, ArrWork* zw) {
   extern __shared__ uint32_t bins_lds[];
   __shared__ uint32_t smax[kMaxF][kThreads / kWave];
   auto bins = [&](int f, int w) { return bins_lds + ((uint32_t)f * (kThreads / kWave) + w) * kResPriv; };
   for (int j = threadIdx.x; j < F * (kThreads / kWave) * kResPriv; j += kThreads) bins_lds[j] = 0;
-  const int r = seg_of_block(pre, R, blockIdx.x);
-  const TFrameDev& fr = T[r];
-  const uint32_t lb = blockIdx.x - pre[r];
-  if (zw && lb == 0 && threadIdx.x < (uint32_t)(F * kWordParts))
-    zw[(uint64_t)r * F + threadIdx.x / kWordParts].huff_words[threadIdx.x % kWordParts] = 0;
-  __syncthreads();
-  const int copy = lb % copies;
-  const uint64_t n = fr.n;
-  const uint64_t item = (uint64_t)lb * kThreads + threadIdx.x;
-  const bool mine = item < (fr.vec ? n / 4 : n);
+  const int copy = blockIdx.x % copies;
+  const uint32_t t0 = (uint32_t)((uint64_t)tiles * blockIdx.x / gridDim.x);
+  const uint32_t t1 = (uint32_t)((uint64_t)tiles * (blockIdx.x + 1) / gridDim.x);
   uint32_t bad = 0;
   uint32_t rmax[kMaxF];
 #pragma unroll
   for (int f = 0; f < kMaxF; f++) rmax[f] = 0;
-  uint32_t idx[4] = {0, 0, 0, 0};
-  if (mine) {
-    if (fr.vec) {
-      const uint4 iv = reinterpret_cast<const uint4*>(fr.perm)[item];
-      idx[0] = iv.x;
-      idx[1] = iv.y;
-      idx[2] = iv.z;
-      idx[3] = iv.w;
-    } else {
-      idx[0] = fr.perm[item];
+  __syncthreads();
+  // the counts, largest value and error bits gathered for frame r so far go
+  // to its arrays; the bins start again from zero
+  auto flush = [&](int r) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) bad |= (uint32_t)__shfl_xor((int)bad, d, kWave);
+    if (lane_id() == 0 && bad) atomicOr(T[r].err, bad);
+    for (int f = 0; f < F; f++) {
+      uint32_t m = rmax[f];
+#pragma unroll
+      for (int d = 1; d < kWave; d <<= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, kWave));
+      if (lane_id() == 0) smax[f][wave_id()] = m;
     }
-  }
-  const int cnt = fr.vec ? 4 : 1;
-  for (int f = 0; f < F; f++) {
-    uint32_t* shared = hist_part + (((uint64_t)r * F + f) * copies + copy) * kAlphabet;
-    uint32_t rv[4] = {0, 0, 0, 0};
-    if (mine) {
-      const uint64_t s0 = fr.vec ? 4 * item : item;
-      for (int u = 0; u < cnt; u++) {
-        int64_t qc, q;
-        t_code(fr.x[f][idx[u]], fr.g, f, &bad, &qc);
-        rv[u] = (uint32_t)zigzag64(
-            t_step(qc, fr.q_ref[(uint64_t)f * n + s0 + u], fr.g.scale, &bad, &q));
-        fr.q_new[(uint64_t)f * n + s0 + u] = (int32_t)q;
-        fr.v8[(uint64_t)f * n + s0 + u] = (uint8_t)min(rv[u], 255u);
-        if (rv[u] >= 255u) fr.esc[(uint64_t)f * n + s0 + u] = rv[u];
-        rmax[f] = max(rmax[f], rv[u]);
+    __syncthreads();
+    for (int f = 0; f < F; f++) {
+      const uint64_t a = (uint64_t)r * F + f;
+      uint32_t* shared = hist_part + (a * copies + copy) * kAlphabet;
+      for (int j = threadIdx.x; j < kResPriv; j += kThreads) {
+        uint32_t t = 0;
+        for (int w = 0; w < kThreads / kWave; w++) {
+          t += bins(f, w)[j];
+          bins(f, w)[j] = 0;
+        }
+        if (t) atomicAdd(&shared[j], t);
+      }
+      if (threadIdx.x == 0) {
+        uint32_t m = 0;
+        for (int w = 0; w < kThreads / kWave; w++) m = max(m, smax[f][w]);
+        if (m) atomicMax(&hist_max[a * copies + copy], (unsigned long long)m);
       }
     }
-    for (int u = 0; u < 4; u++) {
-      int e;
-      wave_hist_add(shared, bins(f, wave_id()), kResPriv, (uint32_t)symbol_of(rv[u], &e),
-                    mine && u < cnt);
-    }
-  }
+    __syncthreads();
+    bad = 0;
 #pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) bad |= (uint32_t)__shfl_xor((int)bad, d, kWave);
-  if (lane_id() == 0 && bad) atomicOr(fr.err, bad);
-  for (int f = 0; f < F; f++) {
-    uint32_t m = rmax[f];
+    for (int f = 0; f < kMaxF; f++) rmax[f] = 0;
+  };
+  int cur = -1;
+  for (uint32_t t = t0; t < t1; t++) {
+    const int r = seg_of_block(pre, R, t);
+    if (r != cur) {
+      if (cur >= 0) flush(cur);
+      cur = r;
+    }
+    const TFrameDev& fr = T[r];
+    const uint32_t lb = t - pre[r];
+    if (zw && lb == 0 && threadIdx.x < (uint32_t)(F * kWordParts))
+      zw[(uint64_t)r * F + threadIdx.x / kWordParts].huff_words[threadIdx.x % kWordParts] = 0;
+    const uint64_t n = fr.n;
+    const uint64_t item = (uint64_t)lb * kThreads + threadIdx.x;
+    const bool mine = item < (fr.vec ? n / 4 : n);
+    uint32_t idx[4] = {0, 0, 0, 0};
+    if (mine) {
+      if (fr.vec) {
+        const uint4 iv = reinterpret_cast<const uint4*>(fr.perm)[item];
+        idx[0] = iv.x;
+        idx[1] = iv.y;
+        idx[2] = iv.z;
+        idx[3] = iv.w;
+      } else {
+        idx[0] = fr.perm[item];
+      }
+    }
+    // four consecutive inputs from a multiple of four: one 16-byte load per field
+    const bool seq4 = fr.vec && mine && (idx[0] & 3u) == 0 && idx[1] == idx[0] + 1 &&
+                      idx[2] == idx[0] + 2 && idx[3] == idx[0] + 3;
+    for (int f = 0; f < F; f++) {
+      uint32_t* shared = hist_part + (((uint64_t)r * F + f) * copies + copy) * kAlphabet;
+      uint32_t rv[4] = {0, 0, 0, 0};
+      if (mine && fr.vec) {
+        const float* x = fr.x[f];
+        float xv[4];
+        if (seq4 && ((uintptr_t)x & 15) == 0) {
+          const float4 v4 = *reinterpret_cast<const float4*>(x + idx[0]);
+          xv[0] = v4.x;
+          xv[1] = v4.y;
+          xv[2] = v4.z;
+          xv[3] = v4.w;
+        } else {
 #pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) m = max(m, (uint32_t)__shfl_xor((int)m, d, kWave));
-    if (lane_id() == 0) smax[f][wave_id()] = m;
-  }
-  __syncthreads();
-  for (int f = 0; f < F; f++) {
-    const uint64_t a = (uint64_t)r * F + f;
-    uint32_t* shared = hist_part + (a * copies + copy) * kAlphabet;
-    for (int j = threadIdx.x; j < kResPriv; j += kThreads) {
-      uint32_t t = 0;
-      for (int w = 0; w < kThreads / kWave; w++) t += bins(f, w)[j];
-      if (t) atomicAdd(&shared[j], t);
+          for (int u = 0; u < 4; u++) xv[u] = x[idx[u]];
+        }
+        const int4 qr = reinterpret_cast<const int4*>(fr.q_ref + (uint64_t)f * n)[item];
+        const int32_t qrv[4] = {qr.x, qr.y, qr.z, qr.w};
+        int32_t qv[4];
+        uint32_t bytes = 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+          int64_t qc, q;
+          t_code(xv[u], fr.g, f, &bad, &qc);
+          rv[u] = (uint32_t)zigzag64(t_step(qc, qrv[u], fr.g.scale, &bad, &q));
+          qv[u] = (int32_t)q;
+          bytes |= min(rv[u], 255u) << (8 * u);
+          rmax[f] = max(rmax[f], rv[u]);
+        }
+        reinterpret_cast<int4*>(fr.q_new + (uint64_t)f * n)[item] = make_int4(qv[0], qv[1], qv[2], qv[3]);
+        reinterpret_cast<uint32_t*>(fr.v8 + (uint64_t)f * n)[item] = bytes;
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+          if (rv[u] >= 255u) fr.esc[(uint64_t)f * n + 4 * item + u] = rv[u];
+      } else if (mine) {
+        int64_t qc, q;
+        t_code(fr.x[f][idx[0]], fr.g, f, &bad, &qc);
+        rv[0] = (uint32_t)zigzag64(t_step(qc, fr.q_ref[(uint64_t)f * n + item], fr.g.scale, &bad, &q));
+        fr.q_new[(uint64_t)f * n + item] = (int32_t)q;
+        fr.v8[(uint64_t)f * n + item] = (uint8_t)min(rv[0], 255u);
+        if (rv[0] >= 255u) fr.esc[(uint64_t)f * n + item] = rv[0];
+        rmax[f] = max(rmax[f], rv[0]);
+      }
+      const int cnt = fr.vec ? 4 : 1;
+      for (int u = 0; u < 4; u++) {
+        int e;
+        wave_hist_add(shared, bins(f, wave_id()), kResPriv, (uint32_t)symbol_of(rv[u], &e),
+                      mine && u < cnt);
+      }
     }
-    if (threadIdx.x == 0) {
-      uint32_t m = 0;
-      for (int w = 0; w < kThreads / kWave; w++) m = max(m, smax[f][w]);
-      if (m) atomicMax(&hist_max[a * copies + copy], (unsigned long long)m);
-    }
   }
+  if (cur >= 0) flush(cur);
 }
 
 // Temporal frames of several streams reconstructed in one launch: workgroup b
@@ -1687,9 +1744,10 @@ void launch_t_resid_multi(const TFrameDev* frames, const uint32_t* pre, uint32_t
                           int F, uint32_t* hist_part, unsigned long long* hist_max, int copies,
                           ArrWork* zero_words, uint64_t bytes, hipStream_t s) {
   if (!blocks) return;
-  launch_timed("t_resid", bytes, k_t_resid_multi, blocks, kThreads,
-               (size_t)F * (kThreads / kWave) * kResPriv * 4, s, frames, pre, R, F, hist_part,
-               hist_max, copies, zero_words);
+  const uint32_t grid = blocks < kMultiGrid ? blocks : kMultiGrid;
+  launch_timed("t_resid", bytes, k_t_resid_multi, grid, kThreads,
+               (size_t)F * (kThreads / kWave) * kResPriv * 4, s, frames, pre, R, F, blocks,
+               hist_part, hist_max, copies, zero_words);
 }
 
 void launch_t_recon_multi(const TReconDev* frames, const uint32_t* pre, uint32_t blocks, int R,

@@ -2582,7 +2582,10 @@ lcp_status serve_t_compress(lcp_plan_s* B, int K, lcp_plan_s* const* plans,
     t.esc = B->v_slot + (uint64_t)F * off;
     t.err = reinterpret_cast<uint32_t*>(B->sret_dev + i);
     t.n = fr.n;
-    t.vec = fr.n % 4 == 0;
+    // the vector path stores four residual bytes and four codes at a time
+    auto a16 = [](const void* q) { return ((uintptr_t)q & 15) == 0; };
+    t.vec = fr.n % 4 == 0 && ((uintptr_t)t.v8 & 3) == 0 && a16(t.q_ref) && a16(t.q_new) &&
+            a16(t.perm);
     t.g = t_grid(*ref, F);
     B->spre_host[i] = blocks;
     blocks += t_multi_blocks(fr.n, t.vec);
