@@ -20,6 +20,7 @@ OK, ERR_ARG, ERR_EB_TOO_SMALL, ERR_RANGE, ERR_CAPACITY, ERR_CORRUPT, ERR_NO_REFE
 EB_ABS, EB_REL_GLOBAL, EB_REL_PER_FIELD = 0, 1, 2
 METHOD_AUTO, METHOD_S, METHOD_T = 0, 1, 2
 DECIDE_S, DECIDE_T, DECIDE_COMPARE = 1, 2, 3
+DTYPE_F32, DTYPE_I32 = 0, 1
 MAX_F = 8
 ALPHABET = 4148
 
@@ -47,12 +48,14 @@ class OracleError(RuntimeError):
 class Params(C.Structure):
     _fields_ = [("eb_mode", C.c_int), ("eb", C.c_double), ("n_fields", C.c_int),
                 ("multi_frame", C.c_int), ("batch_size", C.c_int), ("block_log2", C.c_int),
-                ("chunk_log2", C.c_int), ("anchor_scale", C.c_int), ("n_dims", C.c_int)]
+                ("chunk_log2", C.c_int), ("anchor_scale", C.c_int), ("n_dims", C.c_int),
+                ("dtype", C.c_int)]
 
 
 class Grid(C.Structure):
     _fields_ = [("m", C.c_float), ("eb_q", C.c_float), ("inv", C.c_double),
-                ("eb", C.c_double), ("E", C.c_int)]
+                ("eb", C.c_double), ("E", C.c_int), ("dtype", C.c_int), ("mi", C.c_int32),
+                ("hb", C.c_int64)]
 
 
 class Info(C.Structure):
@@ -63,7 +66,8 @@ class Info(C.Structure):
                 ("coder", C.c_int * (MAX_F + 2)), ("param", C.c_int * (MAX_F + 2)),
                 ("used", C.c_uint32 * (MAX_F + 2)), ("arr_n", C.c_uint64 * (MAX_F + 2)),
                 ("arr_off", C.c_uint64 * (MAX_F + 2)), ("arr_bytes", C.c_uint64 * (MAX_F + 2)),
-                ("scale", C.c_int), ("dims", C.c_int)]
+                ("scale", C.c_int), ("dims", C.c_int), ("dtype", C.c_int),
+                ("mi", C.c_int32 * MAX_F), ("hb", C.c_int64 * MAX_F)]
 
 
 _lib = None
@@ -75,13 +79,18 @@ def lib():
         _lib = C.CDLL(build())
         L = _lib
         P = C.c_void_p
-        L.lco_extent.argtypes = [P, C.c_int, C.c_uint64, P, P]
-        L.lco_field_eb.argtypes = [C.c_int, C.c_double, C.c_int, P, P, P]
+        L.lco_extent.argtypes = [P, C.c_int, C.c_uint64, C.c_int, P, P]
+        L.lco_field_eb.argtypes = [C.c_int, C.c_double, C.c_int, P, P, C.c_int, P]
         L.lco_make_grid.argtypes = [C.c_float, C.c_float, C.c_double, C.POINTER(Grid)]
+        L.lco_make_grid_i.argtypes = [C.c_int32, C.c_double, C.c_int, C.POINTER(Grid)]
         L.lco_quant.argtypes = [C.c_float, C.POINTER(Grid)]
         L.lco_quant.restype = C.c_int64
         L.lco_recon.argtypes = [C.c_int64, C.POINTER(Grid)]
         L.lco_recon.restype = C.c_float
+        L.lco_quant_i.argtypes = [C.c_int32, C.POINTER(Grid)]
+        L.lco_quant_i.restype = C.c_int64
+        L.lco_recon_i.argtypes = [C.c_int64, C.POINTER(Grid)]
+        L.lco_recon_i.restype = C.c_int32
         L.lco_quantize.argtypes = [P, C.c_uint64, C.POINTER(Grid), P]
         L.lco_quantize.restype = None
         L.lco_reconstruct.argtypes = [P, C.c_uint64, C.POINTER(Grid), P]
@@ -129,9 +138,15 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
 
+def dtype_of(fields) -> int:
+    """DTYPE_I32 for int32 fields, DTYPE_F32 otherwise (converted to float32)."""
+    return DTYPE_I32 if np.asarray(fields[0]).dtype == np.int32 else DTYPE_F32
+
+
 def _fields(fields):
-    """List of contiguous float32 arrays + a C array of their pointers (kept alive)."""
-    arrs = [np.ascontiguousarray(f, dtype=np.float32) for f in fields]
+    """Contiguous float32 (or int32) arrays + a C array of their pointers (kept alive)."""
+    dt = np.int32 if dtype_of(fields) == DTYPE_I32 else np.float32
+    arrs = [np.ascontiguousarray(f, dtype=dt) for f in fields]
     ptrs = (C.c_void_p * len(arrs))(*[a.ctypes.data for a in arrs])
     return arrs, ptrs
 
@@ -145,20 +160,22 @@ def _grids(grids):
 
 # ---------------------------------------------------------------- steps
 def extent(fields):
+    """Per-field minima and maxima as float64 (exact for either type)."""
     arrs, ptrs = _fields(fields)
     F = len(arrs)
-    lo = np.zeros(F, np.float32)
-    hi = np.zeros(F, np.float32)
-    _check(lib().lco_extent(ptrs, F, len(arrs[0]), _ptr(lo), _ptr(hi)), "extent")
+    lo = np.zeros(F, np.float64)
+    hi = np.zeros(F, np.float64)
+    _check(lib().lco_extent(ptrs, F, len(arrs[0]), dtype_of(fields), _ptr(lo), _ptr(hi)),
+           "extent")
     return lo, hi
 
 
-def field_eb(eb_mode, eb, lo, hi):
+def field_eb(eb_mode, eb, lo, hi, dtype=DTYPE_F32):
     F = len(lo)
-    lo = np.ascontiguousarray(lo, np.float32)
-    hi = np.ascontiguousarray(hi, np.float32)
+    lo = np.ascontiguousarray(lo, np.float64)
+    hi = np.ascontiguousarray(hi, np.float64)
     out = np.zeros(F, np.float64)
-    _check(lib().lco_field_eb(eb_mode, eb, F, _ptr(lo), _ptr(hi), _ptr(out)), "field_eb")
+    _check(lib().lco_field_eb(eb_mode, eb, F, _ptr(lo), _ptr(hi), dtype, _ptr(out)), "field_eb")
     return out
 
 
@@ -166,6 +183,20 @@ def make_grid(lo, hi, eb_f) -> Grid:
     g = Grid()
     _check(lib().lco_make_grid(float(lo), float(hi), float(eb_f), C.byref(g)), "make_grid")
     return g
+
+
+def make_grid_i(lo, eb_f, s=1) -> Grid:
+    g = Grid()
+    _check(lib().lco_make_grid_i(int(lo), float(eb_f), s, C.byref(g)), "make_grid_i")
+    return g
+
+
+def quant_i(x, g: Grid) -> int:
+    return int(lib().lco_quant_i(int(x), C.byref(g)))
+
+
+def recon_i(q, g: Grid) -> int:
+    return int(lib().lco_recon_i(int(q), C.byref(g)))
 
 
 def quantize(x, g: Grid) -> np.ndarray:
@@ -213,10 +244,14 @@ def bound(F, n, chunk_log2=10) -> int:
     return int(lib().lco_bound(F, n, chunk_log2))
 
 
-def grids_for(fields, eb_mode, eb):
+def grids_for(fields, eb_mode, eb, s=1):
+    """Grids of a frame (float32 grids at eb / s, int32 grids with step s)."""
     lo, hi = extent(fields)
-    ebf = field_eb(eb_mode, eb, lo, hi)
-    return [make_grid(lo[f], hi[f], ebf[f]) for f in range(len(fields))]
+    dt = dtype_of(fields)
+    ebf = field_eb(eb_mode, eb, lo, hi, dt)
+    if dt == DTYPE_I32:
+        return [make_grid_i(int(lo[f]), ebf[f], s) for f in range(len(fields))]
+    return [make_grid(lo[f], hi[f], ebf[f] / s) for f in range(len(fields))]
 
 
 def compress_s(fields, grids, k, chunk_log2=10, seq=0, dims=3):
@@ -254,12 +289,16 @@ def record_info(rec: bytes) -> Info:
     return info
 
 
+def _out_dtype(info):
+    return np.int32 if info.dtype == DTYPE_I32 else np.float32
+
+
 def decompress(rec: bytes, ref_q=None, ref_seq=0):
-    """Returns (fields [F][n] float32 in slot order, q [F][n] int32)."""
+    """Returns (fields [F][n] float32 or int32 in slot order, q [F][n] int32)."""
     info = record_info(rec)
     F, n = info.F, info.n
     buf = np.frombuffer(rec, np.uint8).copy()
-    outs = [np.zeros(n, np.float32) for _ in range(F)]
+    outs = [np.zeros(n, _out_dtype(info)) for _ in range(F)]
     optrs = (C.c_void_p * F)(*[o.ctypes.data for o in outs])
     q = np.zeros((F, n), np.int32)
     nout = C.c_uint64()
@@ -275,7 +314,7 @@ def decompress(rec: bytes, ref_q=None, ref_seq=0):
 
 def search_k(fields, eb_mode, eb, chunk_log2=10, dims=3):
     arrs, ptrs = _fields(fields)
-    p = Params(eb_mode, eb, len(arrs), 0, 0, 0, chunk_log2, 0, dims)
+    p = Params(eb_mode, eb, len(arrs), 0, 0, 0, chunk_log2, 0, dims, dtype_of(fields))
     k = C.c_int()
     sizes = np.zeros(17, np.uint64)
     _check(lib().lco_search_k(ptrs, len(arrs), len(arrs[0]), C.byref(p), C.byref(k),
@@ -287,9 +326,9 @@ class Stream:
     """Alg. 1 multi-frame driver with LCP-FSM (compress and decompress sides)."""
 
     def __init__(self, eb_mode, eb, n_fields=3, multi_frame=1, batch_size=16, block_log2=4,
-                 chunk_log2=10, max_n=1 << 20, anchor_scale=0, n_dims=0):
+                 chunk_log2=10, max_n=1 << 20, anchor_scale=0, n_dims=0, dtype=DTYPE_F32):
         self.p = Params(eb_mode, eb, n_fields, multi_frame, batch_size, block_log2, chunk_log2,
-                        anchor_scale, n_dims)
+                        anchor_scale, n_dims, dtype)
         self.F = n_fields
         self.max_n = max_n
         self.h = lib().lco_stream_create(C.byref(self.p), max_n)
@@ -321,7 +360,7 @@ class Stream:
     def decompress(self, rec: bytes):
         info = record_info(rec)
         buf = np.frombuffer(rec, np.uint8).copy()
-        outs = [np.zeros(info.n, np.float32) for _ in range(info.F)]
+        outs = [np.zeros(info.n, _out_dtype(info)) for _ in range(info.F)]
         optrs = (C.c_void_p * info.F)(*[o.ctypes.data for o in outs])
         nout = C.c_uint64()
         _check(lib().lco_stream_decompress(self.h, _ptr(buf), len(rec), optrs, info.n,
@@ -383,7 +422,7 @@ def container_passes(frames):
 
 
 def container_retrieve(cont: bytes, frames, eb_mode, eb, n_fields=3, block_log2=4,
-                       anchor_scale=0):
+                       anchor_scale=0, dtype=DTYPE_F32):
     """{frame: decoded fields [F][n] in slot order} for the requested frames, and
     the number of records decoded."""
     n, batch, ents = container_entries(cont)
@@ -391,7 +430,7 @@ def container_retrieve(cont: bytes, frames, eb_mode, eb, n_fields=3, block_log2=
     for ps in container_passes(frames):
         need = sorted(set(j for k in ps for j in container_closure(cont, k)))
         st = Stream(eb_mode, eb, n_fields=n_fields, batch_size=batch, block_log2=block_log2,
-                    max_n=max(e[3] for e in ents), anchor_scale=anchor_scale)
+                    max_n=max(e[3] for e in ents), anchor_scale=anchor_scale, dtype=dtype)
         for j in need:
             off, size = ents[j][0], ents[j][1]
             dec = st.decompress(cont[off:off + size])

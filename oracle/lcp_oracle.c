@@ -93,46 +93,59 @@ static int64_t unzigzag(uint64_t z) { return (z & 1) ? -(int64_t)(z >> 1) - 1 : 
 /* ------------------------------------------------------------------ */
 /* a1: extent and error bound                                          */
 /* ------------------------------------------------------------------ */
-int lco_extent(const float* const* x, int F, uint64_t n, float* lo, float* hi) {
+int lco_extent(const void* const* x, int F, uint64_t n, int dtype, double* lo, double* hi) {
   if (F < 1 || F > LCO_MAX_F || n == 0) return LCO_ERR_ARG;
+  if (dtype != LCO_DTYPE_F32 && dtype != LCO_DTYPE_I32) return LCO_ERR_ARG;
   for (int f = 0; f < F; f++) {
-    float a = x[f][0], b = x[f][0];
+    if (dtype == LCO_DTYPE_I32) {
+      const int32_t* v = (const int32_t*)x[f];
+      int32_t a = v[0], b = v[0];
+      for (uint64_t i = 0; i < n; i++) {
+        if (v[i] < a) a = v[i];
+        if (v[i] > b) b = v[i];
+      }
+      lo[f] = (double)a;
+      hi[f] = (double)b;
+      continue;
+    }
+    const float* v = (const float*)x[f];
+    float a = v[0], b = v[0];
     for (uint64_t i = 0; i < n; i++) {
-      float v = x[f][i];
-      if (!isfinite(v)) return LCO_ERR_ARG;
-      if (v < a) a = v;
-      if (v > b) b = v;
+      if (!isfinite(v[i])) return LCO_ERR_ARG;
+      if (v[i] < a) a = v[i];
+      if (v[i] > b) b = v[i];
     }
     /* -0 and +0 compare equal; the extent is taken as +0 so that the origin
      * written to the record does not depend on which zero came first */
-    lo[f] = a == 0.0f ? 0.0f : a;
-    hi[f] = b == 0.0f ? 0.0f : b;
+    lo[f] = a == 0.0f ? 0.0 : (double)a;
+    hi[f] = b == 0.0f ? 0.0 : (double)b;
   }
   return LCO_OK;
 }
 
 /* Value range of D is max(D) - min(D) (Sec. 4, PSNR definition).  The global
  * relative mode takes it over all fields; the per-field mode per field. */
-int lco_field_eb(int eb_mode, double eb, int F, const float* lo, const float* hi,
+int lco_field_eb(int eb_mode, double eb, int F, const double* lo, const double* hi, int dtype,
                  double* eb_f) {
   if (!(eb > 0) || !isfinite(eb)) return LCO_ERR_ARG;
   if (eb_mode == LCO_EB_ABS) {
     for (int f = 0; f < F; f++) eb_f[f] = eb;
   } else if (eb_mode == LCO_EB_REL_GLOBAL) {
-    float a = lo[0], b = hi[0];
+    double a = lo[0], b = hi[0];
     for (int f = 1; f < F; f++) {
       if (lo[f] < a) a = lo[f];
       if (hi[f] > b) b = hi[f];
     }
-    double r = (double)b - (double)a;
+    double r = b - a;
     for (int f = 0; f < F; f++) eb_f[f] = eb * r;
   } else if (eb_mode == LCO_EB_REL_PER_FIELD) {
-    for (int f = 0; f < F; f++) eb_f[f] = eb * ((double)hi[f] - (double)lo[f]);
+    for (int f = 0; f < F; f++) eb_f[f] = eb * (hi[f] - lo[f]);
   } else {
     return LCO_ERR_ARG;
   }
+  /* integers can always be kept exactly: a bound of 0 codes them losslessly */
   for (int f = 0; f < F; f++)
-    if (!(eb_f[f] > 0)) return LCO_ERR_EB_TOO_SMALL;
+    if (dtype == LCO_DTYPE_I32 ? !(eb_f[f] >= 0) : !(eb_f[f] > 0)) return LCO_ERR_EB_TOO_SMALL;
   return LCO_OK;
 }
 
@@ -153,6 +166,8 @@ int lco_make_grid(float lo, float hi, double eb_f, lco_grid* g) {
   float e = (float)t;
   if ((double)e > t) e = nextafterf(e, 0.0f); /* round down */
   if (!(e > 0.0f)) return LCO_ERR_EB_TOO_SMALL;
+  memset(g, 0, sizeof(*g));
+  g->dtype = LCO_DTYPE_F32;
   g->m = lo;
   g->eb_q = e;
   g->inv = 1.0 / (2.0 * (double)e);
@@ -170,6 +185,54 @@ int64_t lco_quant(float x, const lco_grid* g) {
 /* x' = (2q+1) eb_q + m, one rounding to float (fused multiply-add). */
 float lco_recon(int64_t q, const lco_grid* g) {
   return fmaf((float)(2 * q + 1), g->eb_q, g->m);
+}
+
+/* Integer fields (Sec. 3 allows them).  Eq. 5's bins of width 2 eb become runs
+ * of w = 2 hb + 1 consecutive integers from the origin mi, and a value is
+ * reconstructed as the integer at the centre of its run: within hb <= eb of
+ * it, exactly, with no rounding margin.  hb = floor(eb) is the widest such run.
+ * For an anchor whose chained temporal frames move by s bins (Sec. 7.4.2, s
+ * odd) the error of those frames is up to (s w - 1) / 2, so w is the largest
+ * odd integer with s w <= 2 floor(eb) + 1. */
+int lco_make_grid_i(int32_t lo, double eb_f, int s, lco_grid* g) {
+  if (!(eb_f >= 0) || s < 1 || s % 2 == 0) return LCO_ERR_ARG;
+  /* a run of 2^32 - 1 integers covers any int32 field; wider bounds change nothing */
+  int64_t b = eb_f >= 2147483647.0 ? 2147483647 : (int64_t)floor(eb_f);
+  int64_t w = (2 * b + 1) / s;
+  if (w % 2 == 0) w -= 1;
+  if (w < 1) return LCO_ERR_EB_TOO_SMALL;
+  memset(g, 0, sizeof(*g));
+  g->dtype = LCO_DTYPE_I32;
+  g->mi = lo;
+  g->hb = (w - 1) / 2;
+  g->eb = eb_f;
+  return LCO_OK;
+}
+
+/* q = floor((x - mi) / w), exact integer division rounded down. */
+int64_t lco_quant_i(int32_t x, const lco_grid* g) {
+  int64_t d = (int64_t)x - (int64_t)g->mi, w = 2 * g->hb + 1;
+  int64_t q = d / w; /* C rounds toward zero */
+  if (d % w != 0 && d < 0) q -= 1;
+  return q;
+}
+
+/* x' = mi + q w + hb, held to the int32 range: x lies in [INT32_MIN, INT32_MAX],
+ * so a centre outside it moves toward x when clamped and stays within hb. */
+int32_t lco_recon_i(int64_t q, const lco_grid* g) {
+  int64_t v = (int64_t)g->mi + q * (2 * g->hb + 1) + g->hb;
+  if (v > INT32_MAX) v = INT32_MAX;
+  if (v < INT32_MIN) v = INT32_MIN;
+  return (int32_t)v;
+}
+
+/* Code of x[f][i] or of an extent value v on the field's grid, either type. */
+static int64_t quant_at(const void* const* x, int f, uint64_t i, const lco_grid* g) {
+  if (g->dtype == LCO_DTYPE_I32) return lco_quant_i(((const int32_t*)x[f])[i], g);
+  return lco_quant(((const float*)x[f])[i], g);
+}
+static int64_t quant_val(double v, const lco_grid* g) {
+  return g->dtype == LCO_DTYPE_I32 ? lco_quant_i((int32_t)v, g) : lco_quant((float)v, g);
 }
 
 void lco_quantize(const float* x, uint64_t n, const lco_grid* g, int64_t* q) {
@@ -562,11 +625,17 @@ static int write_record(int mode, int scale, int dims, int F, uint64_t n, uint64
   put_u64(out + 32, total);
   for (int d = 0; d < 3; d++) put_u32(out + 40 + 4 * d, bn ? bn[d] : 0);
   put_u8(out + 52, dims == 3 ? 0u : (unsigned)dims); /* spatial dimensions; 0 means 3 */
+  put_u8(out + 53, (unsigned)grids[0].dtype);         /* element type of every field */
   put_u64(out + 56, seq);
   put_u64(out + 64, ref_seq);
   for (int f = 0; f < F; f++) {
-    put_f32(out + HDR_BYTES + 8 * f, grids[f].m);
-    put_f32(out + HDR_BYTES + 8 * f + 4, grids[f].eb_q);
+    if (grids[f].dtype == LCO_DTYPE_I32) {
+      put_u32(out + HDR_BYTES + 8 * f, (uint32_t)grids[f].mi);
+      put_u32(out + HDR_BYTES + 8 * f + 4, (uint32_t)grids[f].hb);
+    } else {
+      put_f32(out + HDR_BYTES + 8 * f, grids[f].m);
+      put_f32(out + HDR_BYTES + 8 * f + 4, grids[f].eb_q);
+    }
   }
   uint64_t off = hdr;
   for (int a = 0; a < A; a++) {
@@ -605,11 +674,11 @@ static int keyidx_cmp(const void* a, const void* b) {
 
 /* bn_d = (qmax_d >> k) + 1 over the D spatial dimensions (1 for the others);
  * the block-id space must stay below 2^63. */
-static int block_counts(const lco_grid* grids, const float* hi, int k, int D, uint32_t* bn) {
+static int block_counts(const lco_grid* grids, const double* hi, int k, int D, uint32_t* bn) {
   unsigned __int128 tot = 1;
   for (int d = 0; d < 3; d++) bn[d] = 1;
   for (int d = 0; d < D; d++) {
-    int64_t qm = lco_quant(hi[d], &grids[d]);
+    int64_t qm = quant_val(hi[d], &grids[d]);
     if (qm < 0 || qm >= Q_LIMIT) return LCO_ERR_RANGE;
     bn[d] = (uint32_t)((qm >> k) + 1);
     tot *= bn[d];
@@ -618,18 +687,20 @@ static int block_counts(const lco_grid* grids, const float* hi, int k, int D, ui
   return LCO_OK;
 }
 
-int lco_compress_s(const float* const* x, int F, int D, uint64_t n, const lco_grid* grids,
+int lco_compress_s(const void* const* x, int F, int D, uint64_t n, const lco_grid* grids,
                    int k, int chunk_log2, uint64_t seq, uint8_t* out, uint64_t cap,
                    uint64_t* size, uint32_t* perm_out, int32_t* q_slot) {
   if (D < 1 || D > 3 || F < D || F > LCO_MAX_F || n == 0 || n > ((uint64_t)1 << 31) || k < 0 ||
       k > 16)
     return LCO_ERR_ARG;
-  float lo[LCO_MAX_F], hi[LCO_MAX_F];
-  int st = lco_extent(x, F, n, lo, hi);
+  for (int f = 1; f < F; f++)
+    if (grids[f].dtype != grids[0].dtype) return LCO_ERR_ARG;
+  double lo[LCO_MAX_F], hi[LCO_MAX_F];
+  int st = lco_extent(x, F, n, grids[0].dtype, lo, hi);
   if (st) return st;
   for (int f = 0; f < F; f++) {
-    if (lco_quant(lo[f], &grids[f]) < 0) return LCO_ERR_ARG; /* grid not from this frame */
-    if (lco_quant(hi[f], &grids[f]) >= Q_LIMIT) return LCO_ERR_RANGE;
+    if (quant_val(lo[f], &grids[f]) < 0) return LCO_ERR_ARG; /* grid not from this frame */
+    if (quant_val(hi[f], &grids[f]) >= Q_LIMIT) return LCO_ERR_RANGE;
   }
   uint32_t bn[3];
   st = block_counts(grids, hi, k, D, bn);
@@ -641,7 +712,7 @@ int lco_compress_s(const float* const* x, int F, int D, uint64_t n, const lco_gr
   keyidx_t* ki = (keyidx_t*)malloc(sizeof(keyidx_t) * n);
   for (uint64_t i = 0; i < n; i++) {
     uint64_t b[3] = {0, 0, 0};
-    for (int d = 0; d < D; d++) b[d] = (uint64_t)lco_quant(x[d][i], &grids[d]) >> k;
+    for (int d = 0; d < D; d++) b[d] = (uint64_t)quant_at(x, d, i, &grids[d]) >> k;
     ki[i].key = b[0] + (uint64_t)bn[0] * (b[1] + (uint64_t)bn[1] * b[2]);
     ki[i].idx = (uint32_t)i;
   }
@@ -676,7 +747,7 @@ int lco_compress_s(const float* const* x, int F, int D, uint64_t n, const lco_gr
     v_rel[d] = (uint64_t*)malloc(sizeof(uint64_t) * n);
     uint64_t prev = 0;
     for (uint64_t s = 0; s < n; s++) {
-      uint64_t q = (uint64_t)lco_quant(x[d][ki[s].idx], &grids[d]);
+      uint64_t q = (uint64_t)quant_at(x, d, ki[s].idx, &grids[d]);
       uint64_t rel = q & (p - 1); /* offset from the block's (0,0,0) corner */
       v_rel[d][s] = (rel - prev) & (p - 1);
       prev = rel;
@@ -685,7 +756,7 @@ int lco_compress_s(const float* const* x, int F, int D, uint64_t n, const lco_gr
   for (int f = D; f < F; f++) {
     v_sup[f] = (uint64_t*)malloc(sizeof(uint64_t) * n);
     for (uint64_t s = 0; s < n; s++)
-      v_sup[f][s] = (uint64_t)lco_quant(x[f][ki[s].idx], &grids[f]);
+      v_sup[f][s] = (uint64_t)quant_at(x, f, ki[s].idx, &grids[f]);
   }
   arr_in arrs[LCO_MAX_F + 2];
   arrs[0].v = v_id;
@@ -707,7 +778,7 @@ int lco_compress_s(const float* const* x, int F, int D, uint64_t n, const lco_gr
   if (st == LCO_OK && q_slot)
     for (int f = 0; f < F; f++)
       for (uint64_t s = 0; s < n; s++)
-        q_slot[(uint64_t)f * n + s] = (int32_t)lco_quant(x[f][ki[s].idx], &grids[f]);
+        q_slot[(uint64_t)f * n + s] = (int32_t)quant_at(x, f, ki[s].idx, &grids[f]);
   for (int d = 0; d < D; d++) free(v_rel[d]);
   for (int f = D; f < F; f++) free(v_sup[f]);
   free(v_id);
@@ -722,23 +793,27 @@ int lco_compress_s(const float* const* x, int F, int D, uint64_t n, const lco_gr
 /* a9: LCP-T -- codes on the reference's grid, in its slot order,      */
 /* minus the reference's codes                                         */
 /* ------------------------------------------------------------------ */
-int lco_compress_t(const float* const* x, int F, uint64_t n, const lco_grid* grids,
+int lco_compress_t(const void* const* x, int F, uint64_t n, const lco_grid* grids,
                    const uint32_t* ref_perm, const int32_t* ref_q, uint64_t ref_seq,
                    int scale, int chunk_log2, uint64_t seq, uint8_t* out, uint64_t cap,
                    uint64_t* size, int32_t* q_slot) {
   if (F < 1 || F > LCO_MAX_F || n == 0 || n > ((uint64_t)1 << 31)) return LCO_ERR_ARG;
   if (scale < 1 || scale > 15 || scale % 2 == 0) return LCO_ERR_ARG;
   if (!ref_perm || !ref_q) return LCO_ERR_NO_REFERENCE;
-  float lo[LCO_MAX_F], hi[LCO_MAX_F];
-  int st = lco_extent(x, F, n, lo, hi);
+  for (int f = 1; f < F; f++)
+    if (grids[f].dtype != grids[0].dtype) return LCO_ERR_ARG;
+  const int is_int = grids[0].dtype == LCO_DTYPE_I32;
+  double lo[LCO_MAX_F], hi[LCO_MAX_F];
+  int st = lco_extent(x, F, n, grids[0].dtype, lo, hi);
   if (st) return st;
   for (int f = 0; f < F; f++) {
-    /* the rounding margin of the inherited grid must still cover this frame */
-    double a = fabs((double)lo[f]), b = fabs((double)hi[f]);
+    /* the rounding margin of the inherited grid must still cover this frame
+     * (float32 output; integer reconstructions are exact) */
+    double a = fabs(lo[f]), b = fabs(hi[f]);
     double M = (a > b ? a : b) + 2.0 * grids[f].eb;
-    if (!(M < ldexp(1.0, grids[f].E))) return LCO_ERR_RANGE;
-    if (lco_quant(lo[f], &grids[f]) < -Q_LIMIT) return LCO_ERR_RANGE;
-    if (lco_quant(hi[f], &grids[f]) >= Q_LIMIT) return LCO_ERR_RANGE;
+    if (!is_int && !(M < ldexp(1.0, grids[f].E))) return LCO_ERR_RANGE;
+    if (quant_val(lo[f], &grids[f]) < -Q_LIMIT) return LCO_ERR_RANGE;
+    if (quant_val(hi[f], &grids[f]) >= Q_LIMIT) return LCO_ERR_RANGE;
   }
   /* Sec. 7.1: quantise the frame, subtract the reference.  With an anchor grid
    * made at eb / s (Sec. 7.4.2) the frame is coded at eb on that finer grid: its
@@ -755,7 +830,7 @@ int lco_compress_t(const float* const* x, int F, uint64_t n, const lco_grid* gri
   }
   for (int f = 0; f < F && st == LCO_OK; f++) {
     for (uint64_t s = 0; s < n; s++) {
-      int64_t q = lco_quant(x[f][ref_perm[s]], &grids[f]);
+      int64_t q = quant_at(x, f, ref_perm[s], &grids[f]);
       int64_t ref = (int64_t)ref_q[(uint64_t)f * n + s];
       int64_t num = q - ref + h;
       /* floor division, exact for negative numerators too */
@@ -791,6 +866,8 @@ int lco_record_info(const uint8_t* rec, uint64_t size, lco_info* info) {
   info->scale = rec[11] ? rec[11] : 1;
   info->dims = rec[52] ? rec[52] : 3;
   if (rec[52] > 2 || (info->mode == 1 && rec[52] != 0)) return LCO_ERR_CORRUPT;
+  info->dtype = rec[53];
+  if (info->dtype != LCO_DTYPE_F32 && info->dtype != LCO_DTYPE_I32) return LCO_ERR_CORRUPT;
   if ((info->mode == 0 && rec[11] != 0) || info->scale > 15 || info->scale % 2 == 0)
     return LCO_ERR_CORRUPT;
   if (info->mode > 1 || info->F < (info->mode == 0 ? info->dims : 1) || info->F > LCO_MAX_F ||
@@ -810,6 +887,13 @@ int lco_record_info(const uint8_t* rec, uint64_t size, lco_info* info) {
     return LCO_ERR_CORRUPT;
   if (info->mode == 0 && (info->B == 0 || info->B > info->n)) return LCO_ERR_CORRUPT;
   for (int f = 0; f < info->F; f++) {
+    if (info->dtype == LCO_DTYPE_I32) {
+      /* origin, then the half width of the integer bins (below 2^31) */
+      info->mi[f] = (int32_t)get_u32(rec + HDR_BYTES + 8 * f);
+      info->hb[f] = get_u32(rec + HDR_BYTES + 8 * f + 4);
+      if (info->hb[f] > INT32_MAX) return LCO_ERR_CORRUPT;
+      continue;
+    }
     info->m[f] = get_f32(rec + HDR_BYTES + 8 * f);
     info->eb_q[f] = get_f32(rec + HDR_BYTES + 8 * f + 4);
     if (!isfinite(info->m[f]) || !(info->eb_q[f] > 0) || !isfinite(info->eb_q[f]))
@@ -839,7 +923,7 @@ static float recon_f(int64_t q, float eb_q, float m) {
 }
 
 int lco_decompress(const uint8_t* rec, uint64_t size, const int32_t* ref_q,
-                   uint64_t ref_seq, uint64_t ref_n, float* const* out, uint64_t cap_n,
+                   uint64_t ref_seq, uint64_t ref_n, void* const* out, uint64_t cap_n,
                    uint64_t* n_out, int32_t* q_slot) {
   lco_info I;
   int st = lco_record_info(rec, size, &I);
@@ -910,9 +994,20 @@ int lco_decompress(const uint8_t* rec, uint64_t size, const int32_t* ref_q,
       }
   }
   if (st == LCO_OK) {
-    for (int f = 0; f < I.F; f++)
-      for (uint64_t t = 0; t < n; t++)
-        out[f][t] = recon_f(q[(uint64_t)f * n + t], I.eb_q[f], I.m[f]);
+    for (int f = 0; f < I.F; f++) {
+      if (I.dtype == LCO_DTYPE_I32) {
+        lco_grid g;
+        memset(&g, 0, sizeof(g));
+        g.dtype = LCO_DTYPE_I32;
+        g.mi = I.mi[f];
+        g.hb = I.hb[f];
+        for (uint64_t t = 0; t < n; t++)
+          ((int32_t*)out[f])[t] = lco_recon_i(q[(uint64_t)f * n + t], &g);
+      } else {
+        for (uint64_t t = 0; t < n; t++)
+          ((float*)out[f])[t] = recon_f(q[(uint64_t)f * n + t], I.eb_q[f], I.m[f]);
+      }
+    }
     if (q_slot) memcpy(q_slot, q, sizeof(int32_t) * n * I.F);
   }
   free(q);
@@ -977,7 +1072,8 @@ lco_stream* lco_stream_create(const lco_params* p, uint64_t max_n) {
       p->n_dims > 3 || p->n_fields < (p->n_dims ? p->n_dims : 3) ||
       p->block_log2 > 16 || p->chunk_log2 < 5 || p->chunk_log2 > 16 || p->batch_size < 0 ||
       max_n == 0 || p->anchor_scale < 0 || p->anchor_scale > 15 ||
-      (p->anchor_scale > 1 && p->anchor_scale % 2 == 0))
+      (p->anchor_scale > 1 && p->anchor_scale % 2 == 0) ||
+      (p->dtype != LCO_DTYPE_F32 && p->dtype != LCO_DTYPE_I32))
     return NULL;
   lco_stream* s = (lco_stream*)calloc(1, sizeof(lco_stream));
   s->p = *p;
@@ -1052,19 +1148,20 @@ int lco_stream_select(const lco_stream* s, int* decision) {
   return LCO_OK;
 }
 
-int lco_stream_compress(lco_stream* s, const float* const* x, uint64_t n, int method,
+int lco_stream_compress(lco_stream* s, const void* const* x, uint64_t n, int method,
                         uint8_t* out, uint64_t cap, uint64_t* size, int* method_used,
                         uint32_t* perm_out) {
   int F = s->p.n_fields;
   if (n == 0 || n > s->max_n || method < 0 || method > 2) return LCO_ERR_ARG;
-  float lo[LCO_MAX_F], hi[LCO_MAX_F];
-  int st = lco_extent(x, F, n, lo, hi);
+  const int is_int = s->p.dtype == LCO_DTYPE_I32;
+  double lo[LCO_MAX_F], hi[LCO_MAX_F];
+  int st = lco_extent(x, F, n, s->p.dtype, lo, hi);
   if (st) return st;
   double eb_f[LCO_MAX_F];
   if (s->p.multi_frame && s->have_eb) {
     memcpy(eb_f, s->eb_f, sizeof(eb_f));
   } else {
-    st = lco_field_eb(s->p.eb_mode, s->p.eb, F, lo, hi, eb_f);
+    st = lco_field_eb(s->p.eb_mode, s->p.eb, F, lo, hi, s->p.dtype, eb_f);
     if (st) return st;
   }
   lco_grid sg[LCO_MAX_F]; /* made only when LCP-S runs: a T frame needs no grid of its own */
@@ -1102,8 +1199,15 @@ int lco_stream_compress(lco_stream* s, const float* const* x, uint64_t n, int me
   if (s->p.multi_frame && s->p.anchor_scale > 1 && first_in_batch(&s->p, s->seq) &&
       (s->n_since_anchor == 0 || 2 * s->t_since_anchor >= s->n_since_anchor))
     s_scale = s->p.anchor_scale;
+  /* an integer bin holds at least one integer: when some field's unscaled bin
+   * has fewer than s integers, no finer anchor grid exists and the anchor is
+   * coded at the stream's bound */
+  for (int f = 0; f < F && is_int && s_scale > 1; f++)
+    if (2 * (eb_f[f] >= 2147483647.0 ? 2147483647 : (int64_t)floor(eb_f[f])) + 1 < s_scale)
+      s_scale = 1;
   for (int f = 0; f < F && st == LCO_OK && need_s; f++)
-    st = lco_make_grid(lo[f], hi[f], eb_f[f] / (double)s_scale, &sg[f]);
+    st = is_int ? lco_make_grid_i((int32_t)lo[f], eb_f[f], s_scale, &sg[f])
+                : lco_make_grid((float)lo[f], (float)hi[f], eb_f[f] / (double)s_scale, &sg[f]);
   if (st == LCO_OK && need_s) {
     bs = (uint8_t*)malloc(bound);
     perm_s = (uint32_t*)malloc(sizeof(uint32_t) * n);
@@ -1172,12 +1276,12 @@ int lco_stream_compress(lco_stream* s, const float* const* x, uint64_t n, int me
 }
 
 int lco_stream_decompress(lco_stream* s, const uint8_t* rec, uint64_t size,
-                          float* const* out, uint64_t cap_n, uint64_t* n_out) {
+                          void* const* out, uint64_t cap_n, uint64_t* n_out) {
   int F = s->p.n_fields;
   lco_info I;
   int st = lco_record_info(rec, size, &I);
   if (st) return st;
-  if (I.F != F || I.n > s->max_n) return LCO_ERR_ARG;
+  if (I.F != F || I.n > s->max_n || I.dtype != s->p.dtype) return LCO_ERR_ARG;
   const ref_t* ref = NULL;
   if (I.mode == 1) {
     if (s->dprev.valid && s->dprev.seq == I.ref_seq) ref = &s->dprev;
@@ -1305,29 +1409,33 @@ int lco_container_closure(const uint8_t* cont, uint64_t size, uint64_t k, uint64
 /* ------------------------------------------------------------------ */
 /* a12: block-size search on a stride sample                           */
 /* ------------------------------------------------------------------ */
-int lco_search_k(const float* const* x, int F, uint64_t n, const lco_params* p, int* k_out,
+int lco_search_k(const void* const* x, int F, uint64_t n, const lco_params* p, int* k_out,
                  uint64_t* sizes) {
   const int D = p->n_dims ? p->n_dims : 3;
   if (D < 1 || D > 3 || F < D || F > LCO_MAX_F || n == 0) return LCO_ERR_ARG;
   uint64_t stride = n >> 20;
   if (stride < 1) stride = 1;
   uint64_t ns = (n + stride - 1) / stride;
-  float* smp[LCO_MAX_F];
+  /* every stride-th value (a 4-byte word of either type) */
+  uint32_t* smp[LCO_MAX_F];
   for (int f = 0; f < F; f++) {
-    smp[f] = (float*)malloc(sizeof(float) * ns);
-    for (uint64_t j = 0; j < ns; j++) smp[f][j] = x[f][j * stride];
+    smp[f] = (uint32_t*)malloc(sizeof(uint32_t) * ns);
+    for (uint64_t j = 0; j < ns; j++) smp[f][j] = ((const uint32_t*)x[f])[j * stride];
   }
-  float lo[LCO_MAX_F], hi[LCO_MAX_F];
+  const int is_int = p->dtype == LCO_DTYPE_I32;
+  double lo[LCO_MAX_F], hi[LCO_MAX_F];
   double eb_f[LCO_MAX_F];
   lco_grid g[LCO_MAX_F];
-  int st = lco_extent((const float* const*)smp, F, ns, lo, hi);
-  if (!st) st = lco_field_eb(p->eb_mode, p->eb, F, lo, hi, eb_f);
-  for (int f = 0; f < F && !st; f++) st = lco_make_grid(lo[f], hi[f], eb_f[f], &g[f]);
+  int st = lco_extent((const void* const*)smp, F, ns, p->dtype, lo, hi);
+  if (!st) st = lco_field_eb(p->eb_mode, p->eb, F, lo, hi, p->dtype, eb_f);
+  for (int f = 0; f < F && !st; f++)
+    st = is_int ? lco_make_grid_i((int32_t)lo[f], eb_f[f], 1, &g[f])
+                : lco_make_grid((float)lo[f], (float)hi[f], eb_f[f], &g[f]);
   int best = -1;
   uint64_t best_size = 0;
   for (int k = 0; k <= 16 && !st; k++) {
     uint64_t sz = 0;
-    int s2 = lco_compress_s((const float* const*)smp, F, D, ns, g, k, p->chunk_log2, 0, NULL, 0,
+    int s2 = lco_compress_s((const void* const*)smp, F, D, ns, g, k, p->chunk_log2, 0, NULL, 0,
                             &sz, NULL, NULL);
     if (sizes) sizes[k] = s2 == LCO_OK ? sz : 0;
     if (s2 == LCO_OK && (best < 0 || sz < best_size)) {

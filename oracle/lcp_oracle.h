@@ -37,6 +37,8 @@ enum {
 enum { LCO_EB_ABS = 0, LCO_EB_REL_GLOBAL = 1, LCO_EB_REL_PER_FIELD = 2 };
 enum { LCO_METHOD_AUTO = 0, LCO_METHOD_S = 1, LCO_METHOD_T = 2 };
 enum { LCO_DECIDE_S = 1, LCO_DECIDE_T = 2, LCO_DECIDE_COMPARE = 3 };
+/* Element type of the input fields (Sec. 3: the data may be integers or floats). */
+enum { LCO_DTYPE_F32 = 0, LCO_DTYPE_I32 = 1 };
 
 #define LCO_MAX_F 8
 
@@ -51,15 +53,20 @@ typedef struct {
   int anchor_scale; /* 0 or 1: off; odd 3..15: an anchor frame is coded at eb / anchor_scale
                        while the stream's temporal correlation is high (Sec. 7.4.2) */
   int n_dims;       /* spatial dimensions 1..3 (0 = 3): the fields that form blocks */
+  int dtype;        /* LCO_DTYPE_F32 or LCO_DTYPE_I32: every field of the stream */
 } lco_params;
 
-/* Quantisation grid of one field (Eq. 5 with the FP32 rounding margin). */
+/* Quantisation grid of one field: Eq. 5 with the FP32 rounding margin for
+ * float32 fields; integer bins for int32 fields. */
 typedef struct {
   float m;       /* origin: the field's minimum on the frame that set the grid */
   float eb_q;    /* half bin width actually used, eb_q <= eb - delta */
   double inv;    /* 1 / (2 * eb_q), double, round-to-nearest */
   double eb;     /* the user's absolute bound for this field */
   int E;         /* magnitude exponent: every |x| + 2 eb < 2^E */
+  int dtype;     /* LCO_DTYPE_*; the members below serve int32 grids only */
+  int32_t mi;    /* origin: the field's minimum */
+  int64_t hb;    /* half bin width, an integer: bins hold 2 hb + 1 integers */
 } lco_grid;
 
 /* Decoded header of a frame record. */
@@ -75,15 +82,28 @@ typedef struct {
   uint64_t arr_n[LCO_MAX_F + 2], arr_off[LCO_MAX_F + 2], arr_bytes[LCO_MAX_F + 2];
   int scale;           /* T records: code step of the residuals (1, or an anchor's scale) */
   int dims;            /* S records: spatial dimensions (fields 0..dims-1 form the blocks) */
+  int dtype;           /* LCO_DTYPE_*: what m/eb_q or mi/hb below describe */
+  int32_t mi[LCO_MAX_F];
+  int64_t hb[LCO_MAX_F];
 } lco_info;
 
 /* ---- step-level entry points (pins and parity at every step) ---- */
-int lco_extent(const float* const* x, int F, uint64_t n, float* lo, float* hi);
-int lco_field_eb(int eb_mode, double eb, int F, const float* lo, const float* hi,
+/* Fields are float32 or int32 arrays (dtype); extents are returned as doubles,
+ * which hold either type exactly. */
+int lco_extent(const void* const* x, int F, uint64_t n, int dtype, double* lo, double* hi);
+/* Absolute bound per field.  An int32 field may get a bound of 0 (a constant
+ * field under a relative mode): it is then coded losslessly. */
+int lco_field_eb(int eb_mode, double eb, int F, const double* lo, const double* hi, int dtype,
                  double* eb_f);
 int lco_make_grid(float lo, float hi, double eb_f, lco_grid* g);
+/* int32 grid for the bound eb_f with the code step s (1, or an anchor's scale):
+ * bins of w = 2 hb + 1 integers with s w <= 2 floor(eb_f) + 1.  LCO_ERR_EB_TOO_SMALL
+ * when no such bin exists (s above 2 floor(eb_f) + 1). */
+int lco_make_grid_i(int32_t lo, double eb_f, int s, lco_grid* g);
 int64_t lco_quant(float x, const lco_grid* g);
 float lco_recon(int64_t q, const lco_grid* g);
+int64_t lco_quant_i(int32_t x, const lco_grid* g);
+int32_t lco_recon_i(int64_t q, const lco_grid* g);
 void lco_quantize(const float* x, uint64_t n, const lco_grid* g, int64_t* q);
 void lco_reconstruct(const int64_t* q, uint64_t n, const lco_grid* g, float* out);
 int lco_huffman_lengths(const uint64_t* counts, int K, uint8_t* len);
@@ -96,24 +116,26 @@ int lco_decode_array(const uint8_t* data, uint64_t nbytes, uint64_t n, int coder
                      int param, uint32_t used, int chunk_log2, uint64_t* v);
 
 /* ---- frame-level compressors ---- */
-/* LCP-S.  grids[F] must be made from this frame's extent.  perm (slot -> input
- * index, [n]) and q_slot ([F][n], slot order) are optional outputs. */
-int lco_compress_s(const float* const* x, int F, int D, uint64_t n, const lco_grid* grids,
+/* LCP-S.  x[F] are float32 or int32 arrays, as grids[0].dtype says.  grids[F]
+ * must be made from this frame's extent.  perm (slot -> input index, [n]) and
+ * q_slot ([F][n], slot order) are optional outputs. */
+int lco_compress_s(const void* const* x, int F, int D, uint64_t n, const lco_grid* grids,
                    int k, int chunk_log2, uint64_t seq, uint8_t* out, uint64_t cap,
                    uint64_t* size, uint32_t* perm, int32_t* q_slot);
 /* LCP-T against a reference (grids, slot permutation, slot-order codes).  scale
  * is 1, or the anchor scale s when the reference grid is an anchor's grid made at
  * eb / s: the frame's codes then move in steps of s on that grid (Sec. 7.4.2). */
-int lco_compress_t(const float* const* x, int F, uint64_t n, const lco_grid* grids,
+int lco_compress_t(const void* const* x, int F, uint64_t n, const lco_grid* grids,
                    const uint32_t* ref_perm, const int32_t* ref_q, uint64_t ref_seq,
                    int scale, int chunk_log2, uint64_t seq, uint8_t* out, uint64_t cap,
                    uint64_t* size, int32_t* q_slot);
 int lco_record_info(const uint8_t* rec, uint64_t size, lco_info* info);
 /* Decode a record.  T records need ref_q ([F][n] slot order) of the frame whose
- * seq equals the record's ref_seq.  out[F] receive float32 in slot order;
- * q_slot ([F][n]) optionally receives the codes. */
+ * seq equals the record's ref_seq.  out[F] receive the values in slot order,
+ * float32 or int32 as the record's dtype says; q_slot ([F][n]) optionally
+ * receives the codes. */
 int lco_decompress(const uint8_t* rec, uint64_t size, const int32_t* ref_q,
-                   uint64_t ref_seq, uint64_t ref_n, float* const* out, uint64_t cap_n,
+                   uint64_t ref_seq, uint64_t ref_n, void* const* out, uint64_t cap_n,
                    uint64_t* n_out, int32_t* q_slot);
 
 /* ---- multi-frame driver (Alg. 1 + LCP-FSM) ---- */
@@ -121,14 +143,14 @@ typedef struct lco_stream lco_stream;
 lco_stream* lco_stream_create(const lco_params* p, uint64_t max_n);
 void lco_stream_destroy(lco_stream* s);
 int lco_stream_select(const lco_stream* s, int* decision);
-int lco_stream_compress(lco_stream* s, const float* const* x, uint64_t n, int method,
+int lco_stream_compress(lco_stream* s, const void* const* x, uint64_t n, int method,
                         uint8_t* out, uint64_t cap, uint64_t* size, int* method_used,
                         uint32_t* perm_out);
 int lco_stream_decompress(lco_stream* s, const uint8_t* rec, uint64_t size,
-                          float* const* out, uint64_t cap_n, uint64_t* n_out);
+                          void* const* out, uint64_t cap_n, uint64_t* n_out);
 
 /* ---- block-size search ---- */
-int lco_search_k(const float* const* x, int F, uint64_t n, const lco_params* p,
+int lco_search_k(const void* const* x, int F, uint64_t n, const lco_params* p,
                  int* k_out, uint64_t* sizes /* [17], 0 = infeasible */);
 
 uint64_t lco_bound(int F, uint64_t n, int chunk_log2);

@@ -4,7 +4,8 @@ These stand in for the paper's datasets (Tab. 1: MD trajectories such as Copper,
 Helium, LJ and YIIP; the HACC cosmology snapshot), which are not available here.
 This module holds no part of the compression method; it only draws inputs, and
 both the GPU library's tests/benchmark and the CPU oracle consume the same arrays.
-Every generator returns float32 structure-of-arrays data shaped (F, n).
+Every generator returns float32 structure-of-arrays data shaped (F, n), except
+the fixed-point one, which returns int32 of the same shape.
 """
 from __future__ import annotations
 
@@ -50,6 +51,13 @@ class MDTrajectory:
             self.pos += self.rng.normal(0.0, self.step, size=self.pos.shape)
         self.t += 1
         return np.ascontiguousarray(self.pos.astype(np.float32))
+
+
+def fixed_point(x: np.ndarray, units_per_length: float = 1000.0) -> np.ndarray:
+    """Integer particle data: positions stored as int32 counts of a fixed length
+    unit (e.g. 1e-3 of the lattice spacing), rounded to nearest."""
+    return np.ascontiguousarray(np.rint(np.asarray(x, np.float64) * units_per_length)
+                                .astype(np.int32))
 
 
 def md_trajectory(n_frames: int, n: int = 1 << 22, dims=(256, 128, 128), seed: int = 2, **kw):

@@ -108,7 +108,11 @@ def parse(rec: bytes, arrays: bool = True) -> dict:
     seq, ref_seq = struct.unpack_from("<QQ", rec, 56)
     assert version == 1 and total == len(rec) and hdr == 80 + 8 * F + 32 * A
     assert A == (F + 2 if mode == 0 else F)
-    grids = [struct.unpack_from("<ff", rec, 80 + 8 * f) for f in range(F)]
+    # byte 53: element type of the fields (0 float32, 1 int32); an int32 grid
+    # slot holds the origin and the half width of the integer bins
+    dtype = rec[53]
+    assert dtype in (0, 1)
+    grids = [struct.unpack_from("<iI" if dtype else "<ff", rec, 80 + 8 * f) for f in range(F)]
     want_arrays, arrays, dirs, off = arrays, [], [], hdr
     for a in range(A):
         coder, param, _r, used, an, aoff, anb = struct.unpack_from("<BBHIQQQ", rec, 80 + 8 * F + 32 * a)
@@ -124,7 +128,8 @@ def parse(rec: bytes, arrays: bool = True) -> dict:
     dims = rec[52] if rec[52] else 3
     assert rec[52] in (0, 1, 2) and (mode == 0 or rec[52] == 0)
     return dict(mode=mode, F=F, k=k, chunk_log2=cl, n=n, B=B, bn=bn, seq=seq, ref_seq=ref_seq,
-                grids=grids, dirs=dirs, arrays=arrays, scale=flags if flags else 1, dims=dims)
+                grids=grids, dirs=dirs, arrays=arrays, scale=flags if flags else 1, dims=dims,
+                dtype=dtype)
 
 
 def s_codes(rec: bytes):
