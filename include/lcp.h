@@ -62,6 +62,8 @@ typedef enum {
 enum { LCP_EB_ABS = 0, LCP_EB_REL_GLOBAL = 1, LCP_EB_REL_PER_FIELD = 2 };
 enum { LCP_METHOD_AUTO = 0, LCP_METHOD_S = 1, LCP_METHOD_T = 2 };
 enum { LCP_DECIDE_S = 1, LCP_DECIDE_T = 2, LCP_DECIDE_COMPARE = 3 };
+/* Element type of a plan's fields (Sec. 3: the data may be integers or floats). */
+enum { LCP_DTYPE_F32 = 0, LCP_DTYPE_I32 = 1 };
 
 typedef struct {
   int eb_mode;        /* LCP_EB_ABS: eb is absolute.  LCP_EB_REL_GLOBAL: eb times the
@@ -97,11 +99,23 @@ typedef struct {
                                    the blocks of Eq. 6 (Sec. 4: data of other dimensions);
                                    at most n_fields; a spatial record carries it in
                                    header byte 52 (3 written as 0) */
+  int dtype;                    /* LCP_DTYPE_F32 (0) or LCP_DTYPE_I32: every field of
+                                   every frame.  int32 fields are quantised to runs of
+                                   2 floor(eb) + 1 consecutive integers and decode to the
+                                   run's centre (held to the int32 range), exact within
+                                   eb; a bound below 1 is lossless, and a relative bound
+                                   of 0 (a constant field) is allowed.  With anchor_scale
+                                   s, an anchor's bins are the widest odd runs with
+                                   s runs <= 2 floor(eb) + 1 integers, and an anchor is
+                                   coded at eb when some field has no such run (bins
+                                   narrower than s).  Records carry it in header byte 53
+                                   and decode only through a plan of the same dtype. */
 } lcp_params;
 
 typedef struct lcp_plan_s* lcp_plan_t;
 
-/* One input frame: fields[0..n_fields) device pointers of n float32 values each. */
+/* One input frame: fields[0..n_fields) device pointers of n float32 values each
+ * (int32 values, the pointers cast, when the plan's dtype is LCP_DTYPE_I32). */
 typedef struct {
   const float* fields[LCP_MAX_FIELDS];
   uint64_t n;
@@ -115,7 +129,7 @@ typedef struct {
 } lcp_blob;
 
 /* Destination of one decompressed frame: n_fields device arrays of `capacity`
- * float32 values each. */
+ * float32 values each (int32 for LCP_DTYPE_I32 plans, the pointers cast). */
 typedef struct {
   float* fields[LCP_MAX_FIELDS];
   uint64_t capacity;

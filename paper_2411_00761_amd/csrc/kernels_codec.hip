@@ -905,8 +905,9 @@ __device__ inline void write_header(const RecHdr& h, uint64_t B, uint64_t size, 
   put64(out, 24, B);
   put64(out, 32, size);
   for (int d = 0; d < 3; d++) put32(out, 40 + 4 * d, h.bn[d]);
-  // byte 52: a spatial record's dimensions (3 written as 0); the rest reserved
-  put32(out, 52, h.mode == 0 && h.dims != 3 ? (uint32_t)h.dims : 0u);
+  // byte 52: a spatial record's dimensions (3 written as 0); byte 53: the
+  // fields' element type (0 float32, 1 int32); the rest reserved
+  put32(out, 52, (h.mode == 0 && h.dims != 3 ? (uint32_t)h.dims : 0u) | ((uint32_t)h.dtype << 8));
   put64(out, 56, h.seq);
   put64(out, 64, h.ref_seq);
   put64(out, 72, 0ull);

@@ -242,10 +242,13 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply4(ScanSet a, uint64_t n,
 // minus the reference codes (zigzag); the new codes become the next reference.
 // The frame must stay inside the grid's float32 margin (|x| + 2 eb < 2^E) and
 // code range (|2q+1| < 2^24); a particle outside it flags the frame.
+// int32 grids have no margin to keep (eb2 = 0, lim = infinity): their
+// reconstructions are exact integers.
 __device__ inline uint32_t t_code(float xv, const GridDev& g, int f, uint32_t* bad, int64_t* qo) {
-  if (!__builtin_isfinite(xv)) *bad |= kErrNonFinite;
-  else if (!(fabs((double)xv) + g.eb2[f] < g.lim[f])) *bad |= kErrRange;
-  int64_t q = quantise(xv, g.m[f], g.inv[f]);
+  const double xd = word_value(xv, g.dtype);
+  if (!g.dtype && !__builtin_isfinite(xv)) *bad |= kErrNonFinite;
+  else if (!(fabs(xd) + g.eb2[f] < g.lim[f])) *bad |= kErrRange;
+  int64_t q = quantise(xd, g.md[f], g.inv[f]);
   if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
     *bad |= kErrRange;
     q = 0;
@@ -745,7 +748,7 @@ __global__ __launch_bounds__(kThreads) void k_t_recon_multi(const TReconDev* T, 
         bad = 1;
         q = 0;
       }
-      fr.out[f][s] = reconstruct(q, fr.eb_q[f], fr.m[f]);
+      fr.out[f][s] = reconstruct(q, fr.eb_q[f], fr.m[f], fr.dtype);
       fr.q_new[(uint64_t)f * n + s] = (int32_t)q;
     }
   }
@@ -790,6 +793,11 @@ __global__ __launch_bounds__(kThreads) void k_extent_b(const SegDev* S, const ui
   const int f = blockIdx.y;
   const float* p = S[r].x[f];
   const uint64_t n = S[r].n;
+  // order-preserving keys: float32 (float_key) or int32 (sign bit flipped)
+  const int is_int = S[r].dtype;
+  auto key_of = [&](float v) {
+    return is_int ? __float_as_uint(v) ^ 0x80000000u : float_key(v);
+  };
   uint32_t mn = 0xFFFFFFFFu, mx = 0u, bad = 0u;
   const uint64_t stride = (uint64_t)nb * blockDim.x;
   const uint64_t t0 = (uint64_t)lb * blockDim.x + threadIdx.x;
@@ -803,19 +811,19 @@ __global__ __launch_bounds__(kThreads) void k_extent_b(const SegDev* S, const ui
     float a[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
     for (int j = 0; j < 4; j++) {
-      uint32_t key = float_key(a[j]);
+      uint32_t key = key_of(a[j]);
       mn = min(mn, key);
       mx = max(mx, key);
-      bad |= !__builtin_isfinite(a[j]);
+      bad |= !is_int && !__builtin_isfinite(a[j]);
     }
   }
   for (uint64_t i = t0; i < head + (n - head) % 4; i += stride) {
     uint64_t idx = i < head ? i : head + 4 * nv + (i - head);
     float v = p[idx];
-    uint32_t key = float_key(v);
+    uint32_t key = key_of(v);
     mn = min(mn, key);
     mx = max(mx, key);
-    bad |= !__builtin_isfinite(v);
+    bad |= !is_int && !__builtin_isfinite(v);
   }
 #pragma unroll
   for (int d = kWave / 2; d > 0; d >>= 1) {
@@ -895,9 +903,9 @@ __global__ __launch_bounds__(kThreads) void k_quant_key_b(const SegDev* S, const
     const uint64_t i = i0 + j;
     if (i < n) {
       const int D = g.D;
-      const uint64_t q0 = (uint64_t)quantise(g.x[0][i], g.m[0], g.inv[0]);
-      const uint64_t q1 = D > 1 ? (uint64_t)quantise(g.x[1][i], g.m[1], g.inv[1]) : 0;
-      const uint64_t q2 = D > 2 ? (uint64_t)quantise(g.x[2][i], g.m[2], g.inv[2]) : 0;
+      const uint64_t q0 = (uint64_t)quantise(word_value(g.x[0][i], g.dtype), g.md[0], g.inv[0]);
+      const uint64_t q1 = D > 1 ? (uint64_t)quantise(word_value(g.x[1][i], g.dtype), g.md[1], g.inv[1]) : 0;
+      const uint64_t q2 = D > 2 ? (uint64_t)quantise(word_value(g.x[2][i], g.dtype), g.md[2], g.inv[2]) : 0;
       const uint64_t b0 = q0 >> k, b1 = q1 >> k, b2 = q2 >> k;
       keys[g.off + i] = (K)(b0 + g.bn0 * (b1 + g.bn1 * b2));  // Eq. 6, x fastest
       vals[g.off + i] = (uint32_t)i;
@@ -908,11 +916,11 @@ __global__ __launch_bounds__(kThreads) void k_quant_key_b(const SegDev* S, const
       if (D == 3) {
 #pragma unroll
         for (int j = 0; j < kMaxF - 3; j++)
-          if (3 + j < F) w[2 + j] = (uint32_t)quantise(g.x[3 + j][i], g.m[3 + j], g.inv[3 + j]);
+          if (3 + j < F) w[2 + j] = (uint32_t)quantise(word_value(g.x[3 + j][i], g.dtype), g.md[3 + j], g.inv[3 + j]);
       } else {
 #pragma unroll
         for (int j = 0; j < kMaxF - 1; j++)
-          if (D + j < F) w[1 + j] = (uint32_t)quantise(g.x[D + j][i], g.m[D + j], g.inv[D + j]);
+          if (D + j < F) w[1 + j] = (uint32_t)quantise(word_value(g.x[D + j][i], g.dtype), g.md[D + j], g.inv[D + j]);
       }
       uint32_t* d = rec + (g.off + i) * (uint64_t)rw;
       if (rw == 2) {
@@ -1210,7 +1218,7 @@ __global__ __launch_bounds__(kThreads) void k_s_recon_b(const uint32_t* blk, con
         bad = true;
         q = 0;
       }
-      g.out[f][s] = reconstruct((int64_t)q, g.eb_q[f], g.m[f]);
+      g.out[f][s] = reconstruct((int64_t)q, g.eb_q[f], g.m[f], g.dtype);
     }
   }
   if (bad) atomicOr(err, kErrCorrupt);
@@ -1268,7 +1276,7 @@ __global__ __launch_bounds__(kThreads) void k_s_recon(const uint32_t* blk, const
         atomicOr(err, kErrCorrupt);
         q = 0;
       }
-      out.p[f][s] = reconstruct((int64_t)q, g.eb_q[f], g.m[f]);
+      out.p[f][s] = reconstruct((int64_t)q, g.eb_q[f], g.m[f], g.dtype);
       if (q_slot) q_slot[(uint64_t)f * n + s] = (int32_t)q;
     }
   }
@@ -1296,7 +1304,7 @@ __global__ __launch_bounds__(kThreads) void k_t_recon(const int32_t* q_ref, int 
             bad = 1;
             q[j] = 0;
           }
-          o[j] = reconstruct(q[j], g.eb_q[f], g.m[f]);
+          o[j] = reconstruct(q[j], g.eb_q[f], g.m[f], g.dtype);
         }
         reinterpret_cast<float4*>(out.p[f])[s4] = make_float4(o[0], o[1], o[2], o[3]);
         if (q_slot)
@@ -1313,7 +1321,7 @@ __global__ __launch_bounds__(kThreads) void k_t_recon(const int32_t* q_ref, int 
           bad = 1;
           q = 0;
         }
-        out.p[f][s] = reconstruct(q, g.eb_q[f], g.m[f]);
+        out.p[f][s] = reconstruct(q, g.eb_q[f], g.m[f], g.dtype);
         if (q_slot) q_slot[(uint64_t)f * n + s] = (int32_t)q;
       }
     }
@@ -1350,7 +1358,7 @@ __global__ __launch_bounds__(kThreads) void k_t_recon_chain(const int32_t* q_ref
               bad = 1;
               q[u] = 0;
             }
-            v[u] = reconstruct(q[u], g.eb_q[f], g.m[f]);
+            v[u] = reconstruct(q[u], g.eb_q[f], g.m[f], g.dtype);
           }
           // written once and not read again here: a streaming (non-temporal) store
           const F4 vv = {v[0], v[1], v[2], v[3]};
@@ -1430,7 +1438,7 @@ __global__ __launch_bounds__(kThreads) void k_t_recon_chain(const int32_t* q_ref
             bad = 1;
             q = 0;
           }
-          out.p[j][f][s] = reconstruct(q, g.eb_q[f], g.m[f]);
+          out.p[j][f][s] = reconstruct(q, g.eb_q[f], g.m[f], g.dtype);
         }
         if (q_last) q_last[(uint64_t)f * n + s] = (int32_t)q;
       }

@@ -53,14 +53,40 @@ __device__ inline int symbol_of(uint64_t v, int* extra) {
   return kDirect + b - kFirstClassBits;
 }
 
-// Eq. 5 on the device: floor(((double)x - (double)m) * inv), IEEE double, no
-// contraction (the build passes -ffp-contract=off).
-__device__ inline int64_t quantise(float x, float m, double inv) {
-  double t = ((double)x - (double)m) * inv;
+// Element types of the input fields: every field of a plan is float32, or
+// every field is int32 (a 4-byte word either way; kernels load the word as a
+// float and reinterpret it for int32 plans).
+constexpr int kDtypeF32 = 0, kDtypeI32 = 1;
+
+// Value of an input word, exact in double for both types.
+__device__ inline double word_value(float w, int is_int) {
+  return is_int ? (double)__float_as_int(w) : (double)w;
+}
+
+// Eq. 5 on the device: floor((x - md) * inv), IEEE double, no contraction (the
+// build passes -ffp-contract=off).  float32 grids: md = m, inv = 1 / (2 eb_q).
+// int32 grids: md = m - 1/2 and inv = 1 / w (rounded) for bins of w integers;
+// then (x - md) = d + 1/2 with d = x - m an integer below 2^33 in magnitude,
+// and (d + 1/2) / w lies at least 1 / (2w) from every integer while the two
+// roundings move it by at most 2^-52 (d + 1/2) / w < 2^-19 / w, so the floor
+// is floor(d / w) exactly.
+__device__ inline int64_t quantise(double x, double md, double inv) {
+  double t = (x - md) * inv;
   return (int64_t)floor(t);
 }
 
-__device__ inline float reconstruct(int64_t q, float eb_q, float m) {
+// Reconstruction as a 4-byte output word.  float32: (2q+1) eb_q + m, one
+// rounding.  int32 (m and eb_q then hold the bits of the origin and of the half
+// width hb): m + q (2 hb + 1) + hb, held to the int32 range, which only moves a
+// value toward its input.
+__device__ inline float reconstruct(int64_t q, float eb_q, float m, int is_int) {
+  if (is_int) {
+    const int64_t hb = (int64_t)__float_as_uint(eb_q);
+    int64_t v = (int64_t)__float_as_int(m) + q * (2 * hb + 1) + hb;
+    v = v > (int64_t)INT32_MAX ? (int64_t)INT32_MAX : v;
+    v = v < (int64_t)INT32_MIN ? (int64_t)INT32_MIN : v;
+    return __int_as_float((int32_t)v);
+  }
   return __builtin_fmaf((float)(2 * q + 1), eb_q, m);
 }
 

@@ -38,10 +38,13 @@ constexpr uint64_t kTimerStride = 16;
 constexpr int kDecSlots = kChainMax;
 
 // ------------------------------------------------------------------ grids
+// int32 grids (dtype kDtypeI32) keep the bits of their origin in m and of
+// their half width in eb_q: the two words the record stores.
 struct HostGrid {
   float m, eb_q;
-  double inv, eb;
+  double md, inv, eb;
   int E;
+  int dtype;
 };
 
 // Eq. 5 with a float32 output.  Every reconstruction of the field lies below
@@ -81,14 +84,42 @@ lcp_status make_grid(float lo, float hi, double eb, HostGrid* g) {
   memcpy(&e, &fb, 4);
   g->m = lo;
   g->eb_q = e;
+  g->md = (double)lo;
   g->inv = 0.5 / (double)e;  // 2 e is exact, so this is the rounding of 1 / (2 e)
   g->eb = eb;
   g->E = E;
+  g->dtype = kDtypeF32;
   return LCP_OK;
 }
 
-int64_t host_quant(float x, const HostGrid& g) {
-  return (int64_t)floor(((double)x - (double)g.m) * g.inv);
+// int32 fields (Sec. 3 allows integer data): a bin is a run of w = 2 hb + 1
+// consecutive integers from the field's minimum and decodes to its centre, an
+// integer within hb of every member, so no rounding margin is needed and
+// hb = floor(eb) (at most 2^31 - 1, enough for any int32 range) is the widest
+// bin the bound allows.  For an anchor whose temporal frames move by s bins
+// (Sec. 7.4.2) their error reaches (s w - 1) / 2, so w is the largest odd
+// integer with s w <= 2 floor(eb) + 1; none exists when that is below s.
+lcp_status make_grid_i(int32_t lo, double eb, int s, HostGrid* g) {
+  if (!(eb >= 0) || s < 1 || !(s & 1)) return LCP_ERR_ARG;
+  const uint64_t b = eb >= 2147483647.0 ? 2147483647ull : (uint64_t)eb;  // eb >= 0: floor
+  uint64_t w = (2 * b + 1) / (uint64_t)s;
+  if (w == 0) return LCP_ERR_EB_TOO_SMALL;
+  if (!(w & 1)) w -= 1;
+  const uint32_t hb = (uint32_t)((w - 1) / 2);
+  memcpy(&g->m, &lo, 4);
+  memcpy(&g->eb_q, &hb, 4);
+  g->md = (double)lo - 0.5;  // see quantise: floor((x - m + 1/2) / w) = floor((x - m) / w)
+  g->inv = 1.0 / (double)w;
+  g->eb = eb;
+  g->E = 0;
+  g->dtype = kDtypeI32;
+  return LCP_OK;
+}
+
+// The code of an extent value (float32 or int32, exact in double), as the
+// device computes it.
+int64_t host_quant(double x, const HostGrid& g) {
+  return (int64_t)floor((x - g.md) * g.inv);
 }
 
 // ------------------------------------------------------------------ device buffers
@@ -358,9 +389,11 @@ GridDev to_dev(const HostGrid* g, int F) {
   GridDev d;
   memset(&d, 0, sizeof(d));
   d.scale = 1;
+  d.dtype = g[0].dtype;
   for (int f = 0; f < F; f++) {
     d.m[f] = g[f].m;
     d.eb_q[f] = g[f].eb_q;
+    d.md[f] = g[f].md;
     d.inv[f] = g[f].inv;
   }
   return d;
@@ -407,9 +440,11 @@ lcp_status upload_segs(lcp_plan_s* P, int R, SegLayout* L, hipStream_t s) {
 
 // ------------------------------------------------------------------ extent
 // Per-field minima and maxima of R frames (seg_host[r].x / .n), one sync.
-lcp_status extent_batch(lcp_plan_s* P, int R, float (*lo)[kMaxF], float (*hi)[kMaxF],
+lcp_status extent_batch(lcp_plan_s* P, int R, double (*lo)[kMaxF], double (*hi)[kMaxF],
                         hipStream_t s) {
   const int F = P->F;
+  const int is_int = P->p.dtype == LCP_DTYPE_I32;
+  for (int r = 0; r < R; r++) P->seg_host[r].dtype = P->p.dtype;
   SegLayout L;
   lcp_status st = upload_segs(P, R, &L, s);
   if (st) return st;
@@ -422,33 +457,52 @@ lcp_status extent_batch(lcp_plan_s* P, int R, float (*lo)[kMaxF], float (*hi)[kM
   const uint32_t* ext = reinterpret_cast<const uint32_t*>(P->ret_host + ext_word0);
   for (int r = 0; r < R; r++)
     for (int f = 0; f < F; f++) {
-      float a = key_float(ext[(size_t)r * 2 * F + 2 * f]);
-      float b = key_float(ext[(size_t)r * 2 * F + 2 * f + 1]);
-      lo[r][f] = a == 0.0f ? 0.0f : a;  // one zero: +0
-      hi[r][f] = b == 0.0f ? 0.0f : b;
+      const uint32_t ka = ext[(size_t)r * 2 * F + 2 * f], kb = ext[(size_t)r * 2 * F + 2 * f + 1];
+      if (is_int) {
+        lo[r][f] = (double)(int32_t)(ka ^ 0x80000000u);
+        hi[r][f] = (double)(int32_t)(kb ^ 0x80000000u);
+        continue;
+      }
+      float a = key_float(ka), b = key_float(kb);
+      lo[r][f] = a == 0.0f ? 0.0 : (double)a;  // one zero: +0
+      hi[r][f] = b == 0.0f ? 0.0 : (double)b;
     }
   return LCP_OK;
 }
 
-lcp_status field_eb(const lcp_params& p, int F, const float* lo, const float* hi, double* eb) {
+// Absolute bound per field.  An int32 field may get 0 (a constant field under
+// a relative bound): it is then kept exactly.
+lcp_status field_eb(const lcp_params& p, int F, const double* lo, const double* hi, double* eb) {
   if (!(p.eb > 0) || !isfinite(p.eb)) return LCP_ERR_ARG;
   if (p.eb_mode == LCP_EB_ABS) {
     for (int f = 0; f < F; f++) eb[f] = p.eb;
   } else if (p.eb_mode == LCP_EB_REL_GLOBAL) {
-    float a = lo[0], b = hi[0];
+    double a = lo[0], b = hi[0];
     for (int f = 1; f < F; f++) {
       a = lo[f] < a ? lo[f] : a;
       b = hi[f] > b ? hi[f] : b;
     }
-    double r = (double)b - (double)a;
-    for (int f = 0; f < F; f++) eb[f] = p.eb * r;
+    for (int f = 0; f < F; f++) eb[f] = p.eb * (b - a);
   } else if (p.eb_mode == LCP_EB_REL_PER_FIELD) {
-    for (int f = 0; f < F; f++) eb[f] = p.eb * ((double)hi[f] - (double)lo[f]);
+    for (int f = 0; f < F; f++) eb[f] = p.eb * (hi[f] - lo[f]);
   } else {
     return LCP_ERR_ARG;
   }
+  const bool is_int = p.dtype == LCP_DTYPE_I32;
   for (int f = 0; f < F; f++)
-    if (!(eb[f] > 0)) return LCP_ERR_EB_TOO_SMALL;
+    if (is_int ? !(eb[f] >= 0) : !(eb[f] > 0)) return LCP_ERR_EB_TOO_SMALL;
+  return LCP_OK;
+}
+
+// The grids of one frame: float32 grids at eb / s, int32 grids with step s.
+lcp_status make_grids(const lcp_params& p, int F, const double* lo, const double* hi,
+                      const double* eb, int s, HostGrid* g) {
+  for (int f = 0; f < F; f++) {
+    lcp_status st = p.dtype == LCP_DTYPE_I32
+                        ? make_grid_i((int32_t)lo[f], eb[f], s, &g[f])
+                        : make_grid((float)lo[f], (float)hi[f], eb[f] / (double)s, &g[f]);
+    if (st) return st;
+  }
   return LCP_OK;
 }
 
@@ -619,6 +673,7 @@ RecHdr make_hdr(int mode, int F, int k, int cl, int A, uint64_t n, uint64_t seq,
   h.n = n;
   h.seq = seq;
   h.ref_seq = ref_seq;
+  h.dtype = g[0].dtype;
   for (int f = 0; f < F; f++) {
     h.m[f] = g[f].m;
     h.eb_q[f] = g[f].eb_q;
@@ -654,7 +709,7 @@ lcp_status capture_graph(lcp_plan_s* P, K& kernels, hipGraphExec_t* exec) {
 // the slot-order codes; perm_dst (nullable, R device pointers, each nullable)
 // the slot -> input permutations; *perm_res the batch's permutation array.
 lcp_status compress_s_batch(lcp_plan_s* P, int R, const HostGrid (*g)[kMaxF],
-                            const float (*hi)[kMaxF], int k, uint64_t seq0, uint8_t* out,
+                            const double (*hi)[kMaxF], int k, uint64_t seq0, uint8_t* out,
                             uint64_t cap, int32_t* q_slot, uint32_t* const* perm_dst,
                             uint64_t* offs, const uint32_t** perm_res, hipStream_t s) {
   const int F = P->F;
@@ -676,8 +731,10 @@ lcp_status compress_s_batch(lcp_plan_s* P, int R, const HostGrid (*g)[kMaxF],
       }
       sg.m[f] = g[r][f].m;
       sg.eb_q[f] = g[r][f].eb_q;
+      sg.md[f] = g[r][f].md;
       sg.inv[f] = g[r][f].inv;
     }
+    sg.dtype = g[r][0].dtype;
     if (tot >= ((unsigned __int128)1 << 63)) return LCP_ERR_RANGE;
     kb[r] = bitwidth64((uint64_t)tot - 1);
     sg.bn0 = bn[0];
@@ -788,14 +845,14 @@ struct SResult {
 };
 
 lcp_status compress_s(lcp_plan_s* P, const float* const* x, uint64_t n, const HostGrid* g,
-                      const float* hi, int k, uint64_t seq, uint8_t* out, uint64_t cap,
+                      const double* hi, int k, uint64_t seq, uint8_t* out, uint64_t cap,
                       int32_t* q_slot, SResult* res, hipStream_t s) {
   for (int f = 0; f < P->F; f++) P->seg_host[0].x[f] = x[f];
   P->seg_host[0].n = n;
   HostGrid g1[1][kMaxF];
-  float h1[1][kMaxF];
+  double h1[1][kMaxF];
   memcpy(g1[0], g, sizeof(HostGrid) * P->F);
-  memcpy(h1[0], hi, sizeof(float) * P->F);
+  memcpy(h1[0], hi, sizeof(double) * P->F);
   uint64_t offs[2] = {0, 0};
   lcp_status st = compress_s_batch(P, 1, g1, h1, k, seq, out, cap, q_slot, nullptr, offs,
                                    &res->perm, s);
@@ -803,15 +860,15 @@ lcp_status compress_s(lcp_plan_s* P, const float* const* x, uint64_t n, const Ho
   return st;
 }
 
-lcp_status extent(lcp_plan_s* P, const float* const* x, uint64_t n, float* lo, float* hi,
+lcp_status extent(lcp_plan_s* P, const float* const* x, uint64_t n, double* lo, double* hi,
                   hipStream_t s) {
   for (int f = 0; f < P->F; f++) P->seg_host[0].x[f] = x[f];
   P->seg_host[0].n = n;
-  float l1[1][kMaxF], h1[1][kMaxF];
+  double l1[1][kMaxF], h1[1][kMaxF];
   lcp_status st = extent_batch(P, 1, l1, h1, s);
   if (st) return st;
-  memcpy(lo, l1[0], sizeof(float) * P->F);
-  memcpy(hi, h1[0], sizeof(float) * P->F);
+  memcpy(lo, l1[0], sizeof(double) * P->F);
+  memcpy(hi, h1[0], sizeof(double) * P->F);
   return LCP_OK;
 }
 
@@ -822,8 +879,10 @@ GridDev t_grid(const RefState& ref, int F) {
   GridDev gd = to_dev(ref.grid, F);
   gd.scale = ref.scale;
   for (int f = 0; f < F; f++) {
-    gd.eb2[f] = 2.0 * ref.grid[f].eb;
-    gd.lim[f] = ldexp(1.0, ref.grid[f].E);
+    // int32 grids: exact integer reconstructions, no float32 margin to keep
+    const bool is_int = ref.grid[f].dtype == kDtypeI32;
+    gd.eb2[f] = is_int ? 0.0 : 2.0 * ref.grid[f].eb;
+    gd.lim[f] = is_int ? HUGE_VAL : ldexp(1.0, ref.grid[f].E);
   }
   return gd;
 }
@@ -1024,13 +1083,17 @@ lcp_status compress_frame(lcp_plan_s* P, const lcp_frame_in& fr, uint8_t* out, u
       (P->n_since_anchor == 0 || 2 * P->t_since_anchor >= P->n_since_anchor))
     s_scale = P->p.anchor_scale;
   if (need_s) {
-    float lo[kMaxF], hi[kMaxF];
+    double lo[kMaxF], hi[kMaxF];
     if ((st = extent(P, fr.fields, n, lo, hi, s))) return st;
     if (multi && P->have_eb) memcpy(eb_f, P->eb_f, sizeof(eb_f));
     else if ((st = field_eb(P->p, F, lo, hi, eb_f))) return st;
+    // an int32 bin holds at least one integer: when a field's unscaled bin has
+    // fewer than s integers there is no finer anchor grid, and the anchor is
+    // coded at the stream's bound
+    for (int f = 0; f < F && s_scale > 1 && P->p.dtype == LCP_DTYPE_I32; f++)
+      if (2.0 * floor(fmin(eb_f[f], 2147483647.0)) + 1.0 < (double)s_scale) s_scale = 1;
     HostGrid sg[kMaxF];
-    for (int f = 0; f < F; f++)
-      if ((st = make_grid(lo[f], hi[f], eb_f[f] / (double)s_scale, &sg[f]))) return st;
+    if ((st = make_grids(P->p, F, lo, hi, eb_f, s_scale, sg))) return st;
     if (multi) {
       qs_i = free_q(P, qt_i);
       ps_i = free_perm(P);
@@ -1281,6 +1344,7 @@ struct ParsedHdr {
   int mode, F, k, cl, A;
   int scale;  // temporal records: residual step (Sec. 7.4.2); 1 for spatial ones
   int dims;   // spatial records: spatial dimensions (byte 52; 3 for temporal ones)
+  int dtype;  // element type of the fields (byte 53)
   uint64_t n, B, total, seq, ref_seq;
   uint32_t bn[3];
   float m[kMaxF], eb_q[kMaxF];
@@ -1312,6 +1376,8 @@ lcp_status parse_header(const uint8_t* b, uint64_t size, ParsedHdr* h) {
   if ((h->mode == 0 && b[11] != 0) || h->scale > 15 || h->scale % 2 == 0) return LCP_ERR_CORRUPT;
   h->dims = b[52] ? b[52] : 3;
   if (b[52] > 2 || (h->mode == 1 && b[52] != 0)) return LCP_ERR_CORRUPT;
+  h->dtype = b[53];
+  if (h->dtype != kDtypeF32 && h->dtype != kDtypeI32) return LCP_ERR_CORRUPT;
   if (h->mode > 1 || h->F < (h->mode == 0 ? h->dims : 1) || h->F > kMaxF || h->k > 16 ||
       h->cl < 5 || h->cl > 16)
     return LCP_ERR_CORRUPT;
@@ -1330,6 +1396,10 @@ lcp_status parse_header(const uint8_t* b, uint64_t size, ParsedHdr* h) {
     uint32_t mb = rd32(b, kHdrBytes + 8 * f), eb = rd32(b, kHdrBytes + 8 * f + 4);
     memcpy(&h->m[f], &mb, 4);
     memcpy(&h->eb_q[f], &eb, 4);
+    if (h->dtype == kDtypeI32) {
+      if (eb > 0x7FFFFFFFu) return LCP_ERR_CORRUPT;  // integer half width below 2^31
+      continue;
+    }
     if (!isfinite(h->m[f]) || !(h->eb_q[f] > 0) || !isfinite(h->eb_q[f])) return LCP_ERR_CORRUPT;
   }
   uint64_t off = hdr;
@@ -1416,6 +1486,7 @@ lcp_status decompress_s_batch(lcp_plan_s* P, const ParsedHdr* H, const lcp_blob*
       return LCP_ERR_CORRUPT;
     DSegDev& g = P->dseg_host[r];
     memset(&g, 0, sizeof(g));
+    g.dtype = h.dtype;
     for (int f = 0; f < F; f++) {
       g.out[f] = outs[r].fields[f];
       g.m[f] = h.m[f];
@@ -1531,7 +1602,8 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
     lcp_status st = parse_header(P->hdr_host + (size_t)kHdrStage * j, blobs[j].size, &H[j]);
     if (st) return st;
     const ParsedHdr& h = H[j];
-    if (h.F != F || h.cl > 12 || h.n > P->N) return LCP_ERR_ARG;
+    // a record of the other element type cannot go to this plan's outputs
+    if (h.F != F || h.cl > 12 || h.n > P->N || h.dtype != P->p.dtype) return LCP_ERR_ARG;
     n_out[j] = h.n;
     if (h.n > outs[j].capacity) return LCP_ERR_CAPACITY;
     for (int f = 0; f < F; f++)
@@ -1641,6 +1713,7 @@ lcp_status decompress_group(lcp_plan_s* P, uint64_t nf, const lcp_blob* blobs,
       GridDev gd;
       memset(&gd, 0, sizeof(gd));
       gd.scale = h.scale;
+      gd.dtype = h.dtype;
       for (int f = 0; f < F; f++) {
         gd.m[f] = h.m[f];
         gd.eb_q[f] = h.eb_q[f];
@@ -1993,12 +2066,12 @@ lcp_status search_k(lcp_plan_s* P, const float* const* sample, uint64_t sn, hipS
       st = LCP_ERR_DEVICE;
     xs[f] = tmp[f];
   }
-  float lo[kMaxF], hi[kMaxF];
+  double lo[kMaxF], hi[kMaxF];
   double eb[kMaxF];
   HostGrid g[kMaxF];
   if (!st) st = extent(P, xs, ns, lo, hi, s);
   if (!st) st = field_eb(P->p, F, lo, hi, eb);
-  for (int f = 0; f < F && !st; f++) st = make_grid(lo[f], hi[f], eb[f], &g[f]);
+  if (!st) st = make_grids(P->p, F, lo, hi, eb, 1, g);
   int best = -1;
   uint64_t best_size = 0;
   for (int k = 0; k <= 16 && !st; k++) {
@@ -2028,9 +2101,9 @@ lcp_status compress_group(lcp_plan_s* P, int R, const lcp_frame_in* fr, uint8_t*
     for (int f = 0; f < F; f++) P->seg_host[r].x[f] = fr[r].fields[f];
     P->seg_host[r].n = fr[r].n;
   }
-  std::vector<float> lo((size_t)R * kMaxF), hi((size_t)R * kMaxF);
-  float(*lo2)[kMaxF] = reinterpret_cast<float(*)[kMaxF]>(lo.data());
-  float(*hi2)[kMaxF] = reinterpret_cast<float(*)[kMaxF]>(hi.data());
+  std::vector<double> lo((size_t)R * kMaxF), hi((size_t)R * kMaxF);
+  double(*lo2)[kMaxF] = reinterpret_cast<double(*)[kMaxF]>(lo.data());
+  double(*hi2)[kMaxF] = reinterpret_cast<double(*)[kMaxF]>(hi.data());
   lcp_status st = extent_batch(P, R, lo2, hi2, s);
   if (st) return st;
   std::vector<HostGrid> g((size_t)R * kMaxF);
@@ -2038,8 +2111,7 @@ lcp_status compress_group(lcp_plan_s* P, int R, const lcp_frame_in* fr, uint8_t*
   for (int r = 0; r < R; r++) {
     double eb[kMaxF];
     if ((st = field_eb(P->p, F, lo2[r], hi2[r], eb))) return st;
-    for (int f = 0; f < F; f++)
-      if ((st = make_grid(lo2[r][f], hi2[r][f], eb[f], &g2[r][f]))) return st;
+    if ((st = make_grids(P->p, F, lo2[r], hi2[r], eb, 1, g2[r]))) return st;
   }
   st = compress_s_batch(P, R, g2, hi2, P->k, P->seq, out, cap, nullptr, perms, offs, nullptr, s);
   if (st) return st;
@@ -2122,7 +2194,8 @@ lcp_status plan_check(const lcp_params& p, const float* const* sample_fields, ui
       p.max_batch_frames < 0 || p.max_batch_frames > kMaxBatch ||
       (p.max_batch_particles != 0 &&
        (p.max_batch_particles < p.max_particles || p.max_batch_particles > 0xFFFFFFFFull)) ||
-      p.anchor_scale < 0 || p.anchor_scale > 15 || (p.anchor_scale > 1 && p.anchor_scale % 2 == 0))
+      p.anchor_scale < 0 || p.anchor_scale > 15 || (p.anchor_scale > 1 && p.anchor_scale % 2 == 0) ||
+      (p.dtype != LCP_DTYPE_F32 && p.dtype != LCP_DTYPE_I32))
     return LCP_ERR_ARG;
   if (p.block_log2 == -1 && (!sample_fields || sample_n == 0 || sample_n > p.max_particles))
     return LCP_ERR_ARG;
@@ -2691,7 +2764,7 @@ lcp_status serve_t_decompress(lcp_plan_s* B, int K, lcp_plan_s* const* plans,
     ParsedHdr& h = H[i];
     if (parse_header(B->hdr_host + (size_t)kHdrStage * i, blobs[i].size, &h)) continue;
     if (h.mode != 1 || h.F != F || h.cl != B->chunk_log2 || P->F != F || h.n > P->N ||
-        h.n > dsts[i].capacity || off + h.n > B->NB)
+        h.dtype != P->p.dtype || h.n > dsts[i].capacity || off + h.n > B->NB)
       continue;
     bool fields = true;
     for (int f = 0; f < F; f++) fields = fields && dsts[i].fields[f];
@@ -2726,6 +2799,7 @@ lcp_status serve_t_decompress(lcp_plan_s* B, int K, lcp_plan_s* const* plans,
     t.q_ref = P->dqpool[refq];
     t.q_new = P->dqpool[dq[i]];
     t.scale = h.scale;
+    t.dtype = h.dtype;
     t.r8 = reinterpret_cast<const int8_t*>(B->dres8 + (uint64_t)F * off);
     for (int f = 0; f < F; f++) {
       t.out[f] = dsts[i].fields[f];

@@ -18,16 +18,20 @@ struct OutPtrs {
   float* p[kMaxF];
 };
 
-// Quantisation grid of every field, by value in kernel arguments.
+// Quantisation grid of every field, by value in kernel arguments.  int32
+// grids keep the bits of their origin in m and of their half width in eb_q
+// (the words the record stores).
 struct GridDev {
   float m[kMaxF];
   float eb_q[kMaxF];
+  double md[kMaxF];   // quantisation origin (see quantise)
   double inv[kMaxF];
   double eb2[kMaxF];  // 2 * the user's bound (temporal feasibility check)
   double lim[kMaxF];  // 2^E: |x| + 2 eb must stay below it on this grid
   // temporal frames: the step of the codes on this grid (1, or the scale of
   // the anchor the grid was made for, Sec. 7.4.2)
-  int32_t scale, pad;
+  int32_t scale;
+  int32_t dtype;  // kDtypeF32 or kDtypeI32
 };
 
 // One symbol array to be coded: u64 or u32 values; its length is n, or
@@ -64,6 +68,7 @@ struct RecHdr {
   int mode, F, k, chunk_log2, A;
   int scale;  // temporal records: residual step (byte 11; 1 is written as 0)
   int dims;   // spatial records: spatial dimensions (byte 52; 3 is written as 0)
+  int dtype;  // element type of the fields (byte 53)
   uint64_t n, seq, ref_seq;
   uint32_t bn[3];
   float m[kMaxF], eb_q[kMaxF];
@@ -103,10 +108,11 @@ uint64_t enc_stage_words(uint64_t n, bool is64, int chunk_log2);
 struct SegDev {
   const float* x[kMaxF];
   float m[kMaxF], eb_q[kMaxF];
-  double inv[kMaxF];
+  double md[kMaxF], inv[kMaxF];
   uint64_t n, off;
   uint64_t bn0, bn1;  // Eq. 6 block grid (1 along axes the data does not have)
   int k, D;           // block size log2, spatial dimensions (fields 0..D-1)
+  int dtype, pad;     // kDtypeF32 or kDtypeI32
 };
 // One frame of a spatial decode batch (device table): frame r owns slots
 // [off, off + n) and blocks [boff, boff + B) of the batch-wide arrays.
@@ -115,7 +121,8 @@ struct DSegDev {
   float m[kMaxF], eb_q[kMaxF];
   uint64_t n, off, B, boff, total_blocks;
   uint64_t bn0, bn1;
-  int k, D;  // block size log2, spatial dimensions
+  int k, D;       // block size log2, spatial dimensions
+  int dtype, pad;  // kDtypeF32 or kDtypeI32
 };
 constexpr int kMaxBatch = 1024;       // frames per spatial batch
 constexpr uint32_t kSegExtCap = 256;  // extent workgroups per frame (at most)
@@ -340,7 +347,7 @@ struct TReconDev {
   float* out[kMaxF];
   uint64_t n;
   float m[kMaxF], eb_q[kMaxF];
-  int32_t scale, pad;
+  int32_t scale, dtype;
 };
 void launch_t_recon_multi(const TReconDev* frames, const uint32_t* pre, uint32_t blocks, int R,
                           int F, uint32_t* err, uint64_t bytes, hipStream_t s);

@@ -21,6 +21,7 @@ MAX_FIELDS = 8
 EB_ABS, EB_REL_GLOBAL, EB_REL_PER_FIELD = 0, 1, 2
 METHOD_AUTO, METHOD_S, METHOD_T = 0, 1, 2
 DECIDE_S, DECIDE_T, DECIDE_COMPARE = 1, 2, 3
+DTYPE_F32, DTYPE_I32 = 0, 1
 
 EXPORTED = ["lcp_plan", "lcp_plan_destroy", "lcp_plan_reset", "lcp_plan_block_log2", "lcp_bound", "lcp_compress",
             "lcp_decompress", "lcp_select", "lcp_status_string", "lcp_kernel_timer_set",
@@ -47,7 +48,7 @@ class lcp_params(C.Structure):
                 ("chunk_log2", C.c_int), ("max_particles", C.c_uint64),
                 ("hbm_budget_bytes", C.c_uint64), ("device", C.c_int),
                 ("max_batch_particles", C.c_uint64), ("max_batch_frames", C.c_int),
-                ("anchor_scale", C.c_int), ("n_dims", C.c_int)]
+                ("anchor_scale", C.c_int), ("n_dims", C.c_int), ("dtype", C.c_int)]
 
 
 class lcp_tuning(C.Structure):
@@ -203,19 +204,23 @@ def _check(st: int, what: str):
 class Plan:
     """lcp_plan / lcp_compress / lcp_decompress / lcp_select on one device.
 
-    frames are torch float32 CUDA tensors shaped (F, n) (rows contiguous)."""
+    frames are torch CUDA tensors shaped (F, n) (rows contiguous): float32, or
+    int32 for a plan made with dtype=DTYPE_I32."""
 
     def __init__(self, eb: float, eb_mode: int = EB_ABS, n_fields: int = 3,
                  multi_frame: bool = False, batch_size: int = 16, block_log2: int = -1,
                  chunk_log2: int = 10, max_particles: int = 1 << 20, hbm_budget_bytes: int = 0,
                  device: int = 0, sample=None, max_batch_particles: int = 0,
-                 max_batch_frames: int = 0, anchor_scale: int = 0, n_dims: int = 0):
+                 max_batch_frames: int = 0, anchor_scale: int = 0, n_dims: int = 0,
+                 dtype: int = DTYPE_F32):
         import torch
         self.F = n_fields
         self.device = device
+        self.tdtype = torch.int32 if dtype == DTYPE_I32 else torch.float32
         self.params = lcp_params(eb_mode, eb, n_fields, int(multi_frame), batch_size, block_log2,
                                  chunk_log2, max_particles, hbm_budget_bytes, device,
-                                 max_batch_particles, max_batch_frames, anchor_scale, n_dims)
+                                 max_batch_particles, max_batch_frames, anchor_scale, n_dims,
+                                 dtype)
         ptrs = None
         sn = 0
         if sample is not None:
@@ -259,7 +264,7 @@ class Plan:
         nf = len(frames)
         frames = [f if f.is_contiguous() else f.contiguous() for f in frames]
         for f in frames:
-            assert f.dtype == torch.float32 and f.is_cuda and f.shape[0] == self.F
+            assert f.dtype == self.tdtype and f.is_cuda and f.shape[0] == self.F
         arr, tab = frame_in_table(frames, self.F, methods)
         cap = 0
         bounds = {}
@@ -285,7 +290,8 @@ class Plan:
         return out, [int(offs[j]) for j in range(nf + 1)], [int(used[j]) for j in range(nf)], perms
 
     def decompress(self, buf, offsets, sizes=None, outs=None):
-        """Decode records at buf[offsets[j]:offsets[j+1]]; returns (F, n) float32 tensors."""
+        """Decode records at buf[offsets[j]:offsets[j+1]]; returns (F, n) tensors of
+        the plan's element type."""
         import torch
         nf = len(offsets) - 1
         offsets = [int(o) for o in offsets]
@@ -294,9 +300,9 @@ class Plan:
             outs = []
             for j in range(nf):
                 n = self.record_n(buf, offsets[j])
-                outs.append(torch.empty((self.F, n), dtype=torch.float32, device=buf.device))
+                outs.append(torch.empty((self.F, n), dtype=self.tdtype, device=buf.device))
         for o in outs:
-            assert o.dtype == torch.float32 and o.stride(1) == 1
+            assert o.dtype == self.tdtype and o.stride(1) == 1
         fo, otab = frame_out_table(outs, self.F)
         n_out = (C.c_uint64 * max(nf, 1))()
         _check(lib().lcp_decompress(self.h, nf, blobs, fo, n_out, _stream_handle()),
@@ -345,7 +351,7 @@ class Plan:
 def compress_static(frames: Sequence, eb: float, eb_mode: int = EB_ABS, n_fields: int = 3,
                     block_log2: int = 4, chunk_log2: int = 10, max_particles: int = 0,
                     max_batch_particles: int = 0, max_batch_frames: int = 0, out=None,
-                    want_perm: bool = False, device: int = 0):
+                    want_perm: bool = False, device: int = 0, dtype: int = DTYPE_F32):
     """lcp_compress_static: LCP-S records of independent frames on the library's
     static scratch (no plan, no allocation inside the call).  Returns
     (out uint8 tensor, offsets list, perms list|None)."""
@@ -354,7 +360,8 @@ def compress_static(frames: Sequence, eb: float, eb_mode: int = EB_ABS, n_fields
     frames = [f if f.is_contiguous() else f.contiguous() for f in frames]
     n_max = max(int(f.shape[1]) for f in frames)
     p = lcp_params(eb_mode, eb, n_fields, 0, 0, block_log2, chunk_log2,
-                   max_particles or n_max, 0, device, max_batch_particles, max_batch_frames)
+                   max_particles or n_max, 0, device, max_batch_particles, max_batch_frames, 0, 0,
+                   dtype)
     if out is None:
         def bound(n):  # worst-case record bytes (what lcp_bound gives)
             w = lambda bits: (bits + 31) // 32  # noqa: E731
@@ -388,7 +395,7 @@ def scratch_bytes(n_fields: int = 3, multi_frame: bool = True, max_particles: in
 class Server:
     """lcp_server_*: multi-frame streams served concurrently on one device.
 
-    Frames are torch float32 CUDA tensors shaped (F, n); records and outputs are
+    Frames are torch float32 (or int32) CUDA tensors shaped (F, n); records and outputs are
     caller tensors kept alive here until their request is waited for."""
 
     def __init__(self, scratch_bytes: int, workers: int = 4, hbm_budget_bytes: int = 0,
@@ -417,9 +424,10 @@ class Server:
 
     def open_stream(self, eb: float, eb_mode: int = EB_ABS, n_fields: int = 3, batch_size: int = 16,
                     block_log2: int = -1, chunk_log2: int = 10, max_particles: int = 1 << 20,
-                    sample=None, anchor_scale: int = 0, n_dims: int = 0) -> int:
+                    sample=None, anchor_scale: int = 0, n_dims: int = 0,
+                    dtype: int = DTYPE_F32) -> int:
         params = lcp_params(eb_mode, eb, n_fields, 1, batch_size, block_log2, chunk_log2,
-                            max_particles, 0, self.device, 0, 0, anchor_scale, n_dims)
+                            max_particles, 0, self.device, 0, 0, anchor_scale, n_dims, dtype)
         ptrs, sn = None, 0
         if sample is not None:
             sample = sample.contiguous()
@@ -463,7 +471,7 @@ class Server:
         rq.stream = stream
         rq.blob.data = buf.data_ptr() + offset
         rq.blob.size = size
-        assert out.is_floating_point() and out.element_size() == 4 and out.stride(1) == 1
+        assert out.element_size() == 4 and out.stride(1) == 1
         ob, row = out.data_ptr(), 4 * out.stride(0)
         for k in range(self.F[stream]):
             rq.dst.fields[k] = ob + row * k
@@ -540,7 +548,8 @@ class Container:
         return [int(arr[i]) for i in range(cnt.value)]
 
     def retrieve(self, plan, frames, outs):
-        """Decode frames (list of ints) into outs (list of (F, n) float32 CUDA tensors);
+        """Decode frames (list of ints) into outs (list of (F, n) CUDA tensors of the
+        plan's element type);
         returns the number of records decoded."""
         n = len(frames)
         fr = (C.c_uint64 * max(n, 1))(*frames)
