@@ -244,17 +244,16 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply4(ScanSet a, uint64_t n,
 // code range (|2q+1| < 2^24); a particle outside it flags the frame.
 // int32 grids have no margin to keep (eb2 = 0, lim = infinity): their
 // reconstructions are exact integers.
-__device__ inline uint32_t t_code(float xv, const GridDev& g, int f, uint32_t* bad, int64_t* qo) {
+__device__ inline void t_code(float xv, const GridDev& g, int f, uint32_t* bad, int32_t* qo) {
   const double xd = word_value(xv, g.dtype);
   if (!g.dtype && !__builtin_isfinite(xv)) *bad |= kErrNonFinite;
   else if (!(fabs(xd) + g.eb2[f] < g.lim[f])) *bad |= kErrRange;
-  int64_t q = quantise(xd, g.md[f], g.inv[f]);
-  if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
+  int32_t q = quantise(xd, g.md[f], g.inv[f]);
+  if (q < -kQLimit || q >= kQLimit) {
     *bad |= kErrRange;
     q = 0;
   }
   *qo = q;
-  return 0;
 }
 
 // Sec. 7.1 with the anchor scale of Sec. 7.4.2: a temporal frame's code on its
@@ -262,16 +261,16 @@ __device__ inline uint32_t t_code(float xv, const GridDev& g, int f, uint32_t* b
 // step s, the multiple nearest the frame's own code q (within (s - 1) / 2 of
 // it, s odd); the residual is that multiple over s.  With s = 1 the code is q
 // itself.  A code outside the code range flags the frame.
-__device__ inline int64_t t_step(int64_t q, int64_t ref, int32_t s, uint32_t* bad, int64_t* qn) {
+// Codes and references lie within +-2^23 here, so every quantity fits 32 bits.
+__device__ inline int32_t t_step(int32_t q, int32_t ref, int32_t s, uint32_t* bad, int32_t* qn) {
   if (s == 1) {
     *qn = q;
     return q - ref;
   }
-  // |q|, |ref| < 2^23 here, so the difference fits 32 bits
-  const int32_t num = (int32_t)(q - ref) + (s - 1) / 2;
+  const int32_t num = q - ref + (s - 1) / 2;
   const int32_t r = num >= 0 ? num / s : -((-num + s - 1) / s);
-  int64_t c = ref + (int64_t)s * r;
-  if (c < -(int64_t)kQLimit || c >= (int64_t)kQLimit) {
+  int32_t c = ref + s * r;
+  if (c < -kQLimit || c >= kQLimit) {
     *bad |= kErrRange;
     c = 0;
   }
@@ -337,9 +336,9 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
         int32_t qv[4];
 #pragma unroll
         for (int j = 0; j < 4; j++) {
-          int64_t q, qn;
+          int32_t q, qn;
           t_code(xv[j], g, f, &bad, &q);
-          rv[j] = (uint32_t)zigzag64(t_step(q, qrv[j], g.scale, &bad, &qn));
+          rv[j] = (uint32_t)zigzag32(t_step(q, qrv[j], g.scale, &bad, &qn));
           qv[j] = (int32_t)qn;
           rmax[f] = max(rmax[f], rv[j]);
         }
@@ -363,10 +362,10 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
     for (uint64_t s = gid; s < n; s += stride) {
       uint32_t i = perm_ref[s];
       for (int f = 0; f < F; f++) {
-        int64_t q0, q;
+        int32_t q0, q;
         t_code(x.p[f][i], g, f, &bad, &q0);
         const uint32_t r =
-            (uint32_t)zigzag64(t_step(q0, q_ref[(uint64_t)f * n + s], g.scale, &bad, &q));
+            (uint32_t)zigzag32(t_step(q0, q_ref[(uint64_t)f * n + s], g.scale, &bad, &q));
         if (v8) {
           v8[(uint64_t)f * n + s] = (uint8_t)min(r, 255u);
           if (r >= 255u) v_res[(uint64_t)f * n + s] = r;
@@ -520,9 +519,9 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
         uint32_t rv[4];
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-          int64_t qc = 0, qn = 0;
+          int32_t qc = 0, qn = 0;
           if (mine) t_code(xv[u], g, f, &bad, &qc);
-          rv[u] = (uint32_t)zigzag64(t_step(qc, q[f][u], g.scale, &bad, &qn));
+          rv[u] = (uint32_t)zigzag32(t_step(qc, q[f][u], g.scale, &bad, &qn));
           q[f][u] = (int32_t)qn;
           if (mine) rmax = max(rmax, rv[u]);
         }
@@ -535,24 +534,28 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
           for (int u = 0; u < 4; u++)
             if (rv[u] >= 255u) oesc[4 * gid + u] = rv[u];
         }
+        HotCounts h{0u, 0u, 0u};
 #pragma unroll
         for (int u = 0; u < 4; u++) {
           int e;
-          wave_hist_add(shared, bins, kRunPriv, (uint32_t)symbol_of(rv[u], &e), mine);
+          hist_add_hot(h, shared, bins, kRunPriv, (uint32_t)symbol_of(rv[u], &e), mine);
         }
+        hist_flush_hot(h, bins);
       } else {
         uint32_t r = 0;
         if (mine) {
-          int64_t qc, qn;
+          int32_t qc, qn;
           t_code(x[idx[0]], g, f, &bad, &qc);
-          r = (uint32_t)zigzag64(t_step(qc, q[f][0], g.scale, &bad, &qn));
+          r = (uint32_t)zigzag32(t_step(qc, q[f][0], g.scale, &bad, &qn));
           q[f][0] = (int32_t)qn;
           out8[gid] = (uint8_t)min(r, 255u);
           if (r >= 255u) oesc[gid] = r;
           rmax = r;
         }
         int e;
-        wave_hist_add(shared, bins, kRunPriv, (uint32_t)symbol_of(r, &e), mine);
+        HotCounts h{0u, 0u, 0u};
+        hist_add_hot(h, shared, bins, kRunPriv, (uint32_t)symbol_of(r, &e), mine);
+        hist_flush_hot(h, bins);
       }
 #pragma unroll
       for (int d = 1; d < kWave; d <<= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, d, kWave));
@@ -696,9 +699,9 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_multi(const TFrameDev* T, 
         uint32_t bytes = 0;
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-          int64_t qc, q;
+          int32_t qc, q;
           t_code(xv[u], fr.g, f, &bad, &qc);
-          rv[u] = (uint32_t)zigzag64(t_step(qc, qrv[u], fr.g.scale, &bad, &q));
+          rv[u] = (uint32_t)zigzag32(t_step(qc, qrv[u], fr.g.scale, &bad, &q));
           qv[u] = (int32_t)q;
           bytes |= min(rv[u], 255u) << (8 * u);
           rmax[f] = max(rmax[f], rv[u]);
@@ -709,9 +712,9 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_multi(const TFrameDev* T, 
         for (int u = 0; u < 4; u++)
           if (rv[u] >= 255u) fr.esc[(uint64_t)f * n + 4 * item + u] = rv[u];
       } else if (mine) {
-        int64_t qc, q;
+        int32_t qc, q;
         t_code(fr.x[f][idx[0]], fr.g, f, &bad, &qc);
-        rv[0] = (uint32_t)zigzag64(t_step(qc, fr.q_ref[(uint64_t)f * n + item], fr.g.scale, &bad, &q));
+        rv[0] = (uint32_t)zigzag32(t_step(qc, fr.q_ref[(uint64_t)f * n + item], fr.g.scale, &bad, &q));
         fr.q_new[(uint64_t)f * n + item] = (int32_t)q;
         fr.v8[(uint64_t)f * n + item] = (uint8_t)min(rv[0], 255u);
         if (rv[0] >= 255u) fr.esc[(uint64_t)f * n + item] = rv[0];
@@ -771,9 +774,9 @@ __global__ __launch_bounds__(kThreads) void k_t_codes(RunFrames fr, int J, int F
   for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < n; s += stride) {
     const uint32_t i = perm_ref[s];
     for (int f = 0; f < F; f++) {
-      int64_t c = g.scale == 1 ? 0 : q_ref[(uint64_t)f * n + s];
+      int32_t c = g.scale == 1 ? 0 : q_ref[(uint64_t)f * n + s];
       for (int j = j0; j < J; j++) {
-        int64_t q;
+        int32_t q;
         t_code(fr.x[j][f][i], g, f, &bad, &q);
         t_step(q, c, g.scale, &bad, &c);
       }

@@ -38,6 +38,9 @@ __host__ __device__ inline int bitwidth64(uint64_t v) {
 __host__ __device__ inline uint64_t zigzag64(int64_t d) {
   return d >= 0 ? (uint64_t)d << 1 : (((uint64_t)(-(d + 1))) << 1) | 1u;
 }
+__host__ __device__ inline uint32_t zigzag32(int32_t d) {
+  return ((uint32_t)d << 1) ^ (uint32_t)(d >> 31);
+}
 __host__ __device__ inline int64_t unzigzag64(uint64_t z) {
   return (z & 1) ? -(int64_t)(z >> 1) - 1 : (int64_t)(z >> 1);
 }
@@ -70,9 +73,12 @@ __device__ inline double word_value(float w, int is_int) {
 // and (d + 1/2) / w lies at least 1 / (2w) from every integer while the two
 // roundings move it by at most 2^-52 (d + 1/2) / w < 2^-19 / w, so the floor
 // is floor(d / w) exactly.
-__device__ inline int64_t quantise(double x, double md, double inv) {
-  double t = (x - md) * inv;
-  return (int64_t)floor(t);
+// The codes in use lie within +-2^23: a value beyond the int32 range (or NaN)
+// is held at its ends, where every caller's range check rejects it, so one
+// saturating 32-bit conversion serves instead of a 64-bit one.
+__device__ inline int32_t quantise(double x, double md, double inv) {
+  const double t = floor((x - md) * inv);
+  return (int32_t)fmin(fmax(t, -2147483648.0), 2147483647.0);
 }
 
 // Reconstruction as a 4-byte output word.  float32: (2q+1) eb_q + m, one
@@ -152,6 +158,29 @@ __device__ inline void wave_hist_add(uint32_t* shared, uint32_t* priv, int n_pri
   uint32_t* bins = sym < (uint32_t)n_priv ? priv : shared;
   if (lane_id() == l) atomicAdd(&bins[sym], (uint32_t)__popcll(m));
   else if (valid && sym != s0) atomicAdd(&bins[sym], 1u);
+}
+
+// A temporally coded frame's residual symbols are nearly all 0, 1 and 2 (the
+// residuals 0, -1 and +1 after zigzag).  The wave counts those three with one
+// ballot each into wave-uniform counters, which stay in scalar registers and
+// reach the bins once per array and frame (hist_flush_hot); the other symbols
+// go through wave_hist_add.  The private bins must hold symbols 0..2.
+struct HotCounts {
+  uint32_t c0, c1, c2;
+};
+__device__ inline void hist_add_hot(HotCounts& h, uint32_t* shared, uint32_t* priv, int n_priv,
+                                    uint32_t sym, bool valid) {
+  h.c0 += (uint32_t)__popcll(__ballot(valid && sym == 0u));
+  h.c1 += (uint32_t)__popcll(__ballot(valid && sym == 1u));
+  h.c2 += (uint32_t)__popcll(__ballot(valid && sym == 2u));
+  wave_hist_add(shared, priv, n_priv, sym, valid && sym > 2u);
+}
+__device__ inline void hist_flush_hot(const HotCounts& h, uint32_t* priv) {
+  if (lane_id() == 0) {
+    if (h.c0) atomicAdd(&priv[0], h.c0);
+    if (h.c1) atomicAdd(&priv[1], h.c1);
+    if (h.c2) atomicAdd(&priv[2], h.c2);
+  }
 }
 
 // Sortable unsigned image of a float (monotone: a < b  <=>  key(a) < key(b)).
