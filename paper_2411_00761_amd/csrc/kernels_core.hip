@@ -7,6 +7,8 @@
 //   expansion and FP32 reconstruction.
 #include <string.h>
 
+#include <type_traits>
+
 #include "lcp_internal.h"
 
 namespace lcp {
@@ -244,16 +246,23 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply4(ScanSet a, uint64_t n,
 // code range (|2q+1| < 2^24); a particle outside it flags the frame.
 // int32 grids have no margin to keep (eb2 = 0, lim = infinity): their
 // reconstructions are exact integers.
-__device__ inline void t_code(float xv, const GridDev& g, int f, uint32_t* bad, int32_t* qo) {
-  const double xd = word_value(xv, g.dtype);
-  if (!g.dtype && !__builtin_isfinite(xv)) *bad |= kErrNonFinite;
-  else if (!(fabs(xd) + g.eb2[f] < g.lim[f])) *bad |= kErrRange;
+// is_int: the grid's type, a constant where the caller is specialised for it.
+// The checks are selects, not branches.
+__device__ inline void t_code_as(float xv, int is_int, const GridDev& g, int f, uint32_t* bad,
+                                 int32_t* qo) {
+  const double xd = word_value(xv, is_int);
+  const bool finite = is_int || __builtin_isfinite(xv);
+  const bool inside = fabs(xd) + g.eb2[f] < g.lim[f];
+  *bad |= (finite ? 0u : (uint32_t)kErrNonFinite) | (finite && !inside ? (uint32_t)kErrRange : 0u);
   int32_t q = quantise(xd, g.md[f], g.inv[f]);
   if (q < -kQLimit || q >= kQLimit) {
     *bad |= kErrRange;
     q = 0;
   }
   *qo = q;
+}
+__device__ inline void t_code(float xv, const GridDev& g, int f, uint32_t* bad, int32_t* qo) {
+  t_code_as(xv, g.dtype, g, f, bad, qo);
 }
 
 // Sec. 7.1 with the anchor scale of Sec. 7.4.2: a temporal frame's code on its
@@ -306,10 +315,10 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
   uint32_t rmax[kMaxF];
 #pragma unroll
   for (int f = 0; f < kMaxF; f++) rmax[f] = 0;
-  auto count = [&](int f, uint32_t r) {
+  auto count = [&](int f, HotCounts& h, uint32_t r) {
     uint32_t* shared = hist_part + ((uint64_t)f * kHistCopies + copy) * kAlphabet;
     int e;
-    wave_hist_add(shared, bins(f, wave_id()), kResPriv, (uint32_t)symbol_of(r, &e), true);
+    hist_add_hot(h, shared, bins(f, wave_id()), kResPriv, (uint32_t)symbol_of(r, &e), true);
   };
   if (vec) {  // n % 4 == 0 and 16-byte aligned arrays: 4 slots per thread
     for (uint64_t s4 = gid; s4 < n / 4; s4 += stride) {
@@ -354,8 +363,10 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
           reinterpret_cast<uint4*>(v_res + (uint64_t)f * n)[s4] = make_uint4(rv[0], rv[1], rv[2], rv[3]);
         }
         reinterpret_cast<int4*>(q_new + (uint64_t)f * n)[s4] = make_int4(qv[0], qv[1], qv[2], qv[3]);
+        HotCounts h{0u, 0u, 0u};
 #pragma unroll
-        for (int j = 0; j < 4; j++) count(f, rv[j]);
+        for (int j = 0; j < 4; j++) count(f, h, rv[j]);
+        hist_flush_hot(h, bins(f, wave_id()));
       }
     }
   } else {
@@ -374,7 +385,9 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
         }
         q_new[(uint64_t)f * n + s] = (int32_t)q;
         rmax[f] = max(rmax[f], r);
-        count(f, r);
+        HotCounts h{0u, 0u, 0u};
+        count(f, h, r);
+        hist_flush_hot(h, bins(f, wave_id()));
       }
     }
   }
@@ -419,7 +432,7 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
 // [a copies, (a + 1) copies), work record zw[a]; frame j's error word at
 // err + j * err_stride.
 constexpr int kRunPriv = 128;
-template <int F>
+template <int F, int DT>
 __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, uint64_t n,
                                                           GridDev g, const uint32_t* perm,
                                                           const int32_t* q_ref, int32_t* q_last,
@@ -520,7 +533,7 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
 #pragma unroll
         for (int u = 0; u < 4; u++) {
           int32_t qc = 0, qn = 0;
-          if (mine) t_code(xv[u], g, f, &bad, &qc);
+          if (mine) t_code_as(xv[u], DT, g, f, &bad, &qc);
           rv[u] = (uint32_t)zigzag32(t_step(qc, q[f][u], g.scale, &bad, &qn));
           q[f][u] = (int32_t)qn;
           if (mine) rmax = max(rmax, rv[u]);
@@ -545,7 +558,7 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
         uint32_t r = 0;
         if (mine) {
           int32_t qc, qn;
-          t_code(x[idx[0]], g, f, &bad, &qc);
+          t_code_as(x[idx[0]], DT, g, f, &bad, &qc);
           r = (uint32_t)zigzag32(t_step(qc, q[f][0], g.scale, &bad, &qn));
           q[f][0] = (int32_t)qn;
           out8[gid] = (uint8_t)min(r, 255u);
@@ -721,11 +734,13 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_multi(const TFrameDev* T, 
         rmax[f] = max(rmax[f], rv[0]);
       }
       const int cnt = fr.vec ? 4 : 1;
+      HotCounts h{0u, 0u, 0u};
       for (int u = 0; u < 4; u++) {
         int e;
-        wave_hist_add(shared, bins(f, wave_id()), kResPriv, (uint32_t)symbol_of(rv[u], &e),
-                      mine && u < cnt);
+        hist_add_hot(h, shared, bins(f, wave_id()), kResPriv, (uint32_t)symbol_of(rv[u], &e),
+                     mine && u < cnt);
       }
+      hist_flush_hot(h, bins(f, wave_id()));
     }
   }
   if (cur >= 0) flush(cur);
@@ -1728,17 +1743,24 @@ void launch_t_resid_run(const RunFrames& fr, int J, int F, uint64_t n, const Gri
   // frames read and their residual bytes written, the permutation and the first
   // reference codes read and the last codes written once -- since the codes
   // stay in registers from frame to frame
-  auto* kernel = k_t_resid_run<3>;
-  switch (F) {
-    case 1: kernel = k_t_resid_run<1>; break;
-    case 2: kernel = k_t_resid_run<2>; break;
-    case 4: kernel = k_t_resid_run<4>; break;
-    case 5: kernel = k_t_resid_run<5>; break;
-    case 6: kernel = k_t_resid_run<6>; break;
-    case 7: kernel = k_t_resid_run<7>; break;
-    case 8: kernel = k_t_resid_run<8>; break;
-    default: break;
-  }
+  // one instance per field count and element type
+  auto pick = [&](auto dt) {
+    constexpr int D = decltype(dt)::value;
+    auto* k = k_t_resid_run<3, D>;
+    switch (F) {
+      case 1: k = k_t_resid_run<1, D>; break;
+      case 2: k = k_t_resid_run<2, D>; break;
+      case 4: k = k_t_resid_run<4, D>; break;
+      case 5: k = k_t_resid_run<5, D>; break;
+      case 6: k = k_t_resid_run<6, D>; break;
+      case 7: k = k_t_resid_run<7, D>; break;
+      case 8: k = k_t_resid_run<8, D>; break;
+      default: break;
+    }
+    return k;
+  };
+  auto* kernel = g.dtype == kDtypeI32 ? pick(std::integral_constant<int, kDtypeI32>())
+                                      : pick(std::integral_constant<int, kDtypeF32>());
   launch_timed("t_resid_run", n * (uint64_t)J * (4 + 12ull * F), kernel,
                grid_for(items, kThreads, 1u << 24), kThreads,
                (size_t)J * F * kRunPriv * 4, s, fr, J, n, g, perm, q_ref,

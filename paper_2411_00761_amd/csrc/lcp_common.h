@@ -150,11 +150,11 @@ __device__ inline T block_incl_scan(T v, T* sm, T* total) {
 // `shared`.
 __device__ inline void wave_hist_add(uint32_t* shared, uint32_t* priv, int n_priv, uint32_t sym,
                                      bool valid) {
-  const uint64_t todo = __ballot(valid);
+  const uint64_t todo = __builtin_amdgcn_ballot_w64(valid);
   if (!todo) return;
   const int l = __ffsll((long long)todo) - 1;
   const uint32_t s0 = (uint32_t)__builtin_amdgcn_readlane((int)sym, l);
-  const uint64_t m = __ballot(valid && sym == s0);
+  const uint64_t m = __builtin_amdgcn_ballot_w64(valid && sym == s0);
   uint32_t* bins = sym < (uint32_t)n_priv ? priv : shared;
   if (lane_id() == l) atomicAdd(&bins[sym], (uint32_t)__popcll(m));
   else if (valid && sym != s0) atomicAdd(&bins[sym], 1u);
@@ -170,13 +170,16 @@ struct HotCounts {
 };
 __device__ inline void hist_add_hot(HotCounts& h, uint32_t* shared, uint32_t* priv, int n_priv,
                                     uint32_t sym, bool valid) {
-  h.c0 += (uint32_t)__popcll(__ballot(valid && sym == 0u));
-  h.c1 += (uint32_t)__popcll(__ballot(valid && sym == 1u));
-  h.c2 += (uint32_t)__popcll(__ballot(valid && sym == 2u));
+  // the bool ballot takes the compare mask as it is (no 0/1 round trip)
+  h.c0 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(valid && sym == 0u));
+  h.c1 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(valid && sym == 1u));
+  h.c2 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(valid && sym == 2u));
   wave_hist_add(shared, priv, n_priv, sym, valid && sym > 2u);
 }
 __device__ inline void hist_flush_hot(const HotCounts& h, uint32_t* priv) {
-  if (lane_id() == 0) {
+  // one lane adds them: the first active one (a grid-stride loop's last
+  // iteration may have left out the low lanes)
+  if (lane_id() == __ffsll((long long)__ballot(1)) - 1) {
     if (h.c0) atomicAdd(&priv[0], h.c0);
     if (h.c1) atomicAdd(&priv[1], h.c1);
     if (h.c2) atomicAdd(&priv[2], h.c2);
