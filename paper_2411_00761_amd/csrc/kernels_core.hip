@@ -317,20 +317,18 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
   for (int f = 0; f < kMaxF; f++) rmax[f] = 0;
   auto count = [&](int f, HotCounts& h, uint32_t r) {
     uint32_t* shared = hist_part + ((uint64_t)f * kHistCopies + copy) * kAlphabet;
-    int e;
-    hist_add_hot(h, shared, bins(f, wave_id()), kResPriv, (uint32_t)symbol_of(r, &e), true);
+    hist_add_hot(h, shared, bins(f, wave_id()), kResPriv, r, true);
   };
   if (vec) {  // n % 4 == 0 and 16-byte aligned arrays: 4 slots per thread
     for (uint64_t s4 = gid; s4 < n / 4; s4 += stride) {
       const uint4 iv = reinterpret_cast<const uint4*>(perm_ref)[s4];
       const uint32_t idx[4] = {iv.x, iv.y, iv.z, iv.w};
-      // consecutive inputs from a multiple of four: one 16-byte load per field
-      const bool seq4 = (idx[0] & 3u) == 0 && idx[1] == idx[0] + 1 && idx[2] == idx[0] + 2 &&
-                        idx[3] == idx[0] + 3;
+      // four consecutive inputs: one 16-byte load per field (see float4_a4)
+      const bool seq4 = idx[1] == idx[0] + 1 && idx[2] == idx[0] + 2 && idx[3] == idx[0] + 3;
       for (int f = 0; f < F; f++) {
         float xv[4];
-        if (seq4 && ((uintptr_t)x.p[f] & 15) == 0) {
-          const float4 v4 = *reinterpret_cast<const float4*>(x.p[f] + idx[0]);
+        if (seq4 && ((uintptr_t)x.p[f] & 3) == 0) {
+          const float4_a4 v4 = *reinterpret_cast<const float4_a4*>(x.p[f] + idx[0]);
           xv[0] = v4.x;
           xv[1] = v4.y;
           xv[2] = v4.z;
@@ -469,11 +467,12 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
       idx[0] = perm[gid];
     }
   }
-  // four slots whose inputs are four consecutive values from a multiple of
-  // four (a slot order that keeps runs of the input order, as a trajectory's
-  // does) are read with one 16-byte load per field instead of four gathers
-  const bool seq4 = vec && mine && (idx[0] & 3u) == 0 && idx[1] == idx[0] + 1 &&
-                    idx[2] == idx[0] + 2 && idx[3] == idx[0] + 3;
+  // four slots whose inputs are four consecutive values (a slot order that
+  // keeps runs of the input order, as a trajectory's does) are read with one
+  // 16-byte load per field instead of four gathers, wherever the run starts
+  // (see float4_a4)
+  const bool seq4 = vec && mine && idx[1] == idx[0] + 1 && idx[2] == idx[0] + 2 &&
+                    idx[3] == idx[0] + 3;
 #pragma unroll
   for (int f = 0; f < F; f++) {
     q[f][0] = q[f][1] = q[f][2] = q[f][3] = 0;
@@ -496,8 +495,8 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
 #pragma unroll
     for (int f = 0; f < F; f++) {
       const float* x = fr.x[j][f];
-      if (seq4 && ((uintptr_t)x & 15) == 0) {
-        const float4 v4 = *reinterpret_cast<const float4*>(x + idx[0]);
+      if (seq4 && ((uintptr_t)x & 3) == 0) {
+        const float4_a4 v4 = *reinterpret_cast<const float4_a4*>(x + idx[0]);
         xn[f][0] = v4.x;
         xn[f][1] = v4.y;
         xn[f][2] = v4.z;
@@ -526,7 +525,8 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
       const float* x = fr.x[j][f];
       uint8_t* out8 = v8 + a * astride;
       uint32_t* oesc = vesc + a * astride;
-      uint32_t rmax = 0;
+      uint32_t rmax = 0;  // the lane's largest residual of this array
+      HotCounts h{0u, 0u, 0u};
       if (vec) {
         const float* xv = xc[f];
         uint32_t rv[4];
@@ -536,24 +536,21 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
           if (mine) t_code_as(xv[u], DT, g, f, &bad, &qc);
           rv[u] = (uint32_t)zigzag32(t_step(qc, q[f][u], g.scale, &bad, &qn));
           q[f][u] = (int32_t)qn;
-          if (mine) rmax = max(rmax, rv[u]);
         }
         if (mine) {
+          rmax = max(max(rv[0], rv[1]), max(rv[2], rv[3]));
           uint32_t bytes = 0;
 #pragma unroll
           for (int u = 0; u < 4; u++) bytes |= min(rv[u], 255u) << (8 * u);
           reinterpret_cast<uint32_t*>(out8)[gid] = bytes;
+          if (rmax >= 255u) {
 #pragma unroll
-          for (int u = 0; u < 4; u++)
-            if (rv[u] >= 255u) oesc[4 * gid + u] = rv[u];
+            for (int u = 0; u < 4; u++)
+              if (rv[u] >= 255u) oesc[4 * gid + u] = rv[u];
+          }
         }
-        HotCounts h{0u, 0u, 0u};
 #pragma unroll
-        for (int u = 0; u < 4; u++) {
-          int e;
-          hist_add_hot(h, shared, bins, kRunPriv, (uint32_t)symbol_of(rv[u], &e), mine);
-        }
-        hist_flush_hot(h, bins);
+        for (int u = 0; u < 4; u++) hist_add_hot(h, shared, bins, kRunPriv, rv[u], mine);
       } else {
         uint32_t r = 0;
         if (mine) {
@@ -565,18 +562,14 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
           if (r >= 255u) oesc[gid] = r;
           rmax = r;
         }
-        int e;
-        HotCounts h{0u, 0u, 0u};
-        hist_add_hot(h, shared, bins, kRunPriv, (uint32_t)symbol_of(r, &e), mine);
-        hist_flush_hot(h, bins);
+        hist_add_hot(h, shared, bins, kRunPriv, r, mine);
       }
-#pragma unroll
-      for (int d = 1; d < kWave; d <<= 1) rmax = max(rmax, (uint32_t)__shfl_xor((int)rmax, d, kWave));
-      if (lane_id() == 0 && rmax) atomicMax(&smax[j][f], rmax);
+      hist_flush_hot(h, bins);
+      const uint32_t wmax = wave_max_hot(h, rmax);
+      if (lane_id() == 0 && wmax) atomicMax(&smax[j][f], wmax);
     }
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) bad |= (uint32_t)__shfl_xor((int)bad, d, kWave);
-    if (lane_id() == 0 && bad) atomicOr(err + (uint64_t)j * err_stride, bad);
+    // the frame's error flags: each flagged lane reports its own (rare)
+    if (bad) atomicOr(err + (uint64_t)j * err_stride, bad);
   }
   if (mine && q_last) {
 #pragma unroll
@@ -687,17 +680,17 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_multi(const TFrameDev* T, 
         idx[0] = fr.perm[item];
       }
     }
-    // four consecutive inputs from a multiple of four: one 16-byte load per field
-    const bool seq4 = fr.vec && mine && (idx[0] & 3u) == 0 && idx[1] == idx[0] + 1 &&
-                      idx[2] == idx[0] + 2 && idx[3] == idx[0] + 3;
+    // four consecutive inputs: one 16-byte load per field (see float4_a4)
+    const bool seq4 = fr.vec && mine && idx[1] == idx[0] + 1 && idx[2] == idx[0] + 2 &&
+                      idx[3] == idx[0] + 3;
     for (int f = 0; f < F; f++) {
       uint32_t* shared = hist_part + (((uint64_t)r * F + f) * copies + copy) * kAlphabet;
       uint32_t rv[4] = {0, 0, 0, 0};
       if (mine && fr.vec) {
         const float* x = fr.x[f];
         float xv[4];
-        if (seq4 && ((uintptr_t)x & 15) == 0) {
-          const float4 v4 = *reinterpret_cast<const float4*>(x + idx[0]);
+        if (seq4 && ((uintptr_t)x & 3) == 0) {
+          const float4_a4 v4 = *reinterpret_cast<const float4_a4*>(x + idx[0]);
           xv[0] = v4.x;
           xv[1] = v4.y;
           xv[2] = v4.z;
@@ -735,11 +728,8 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_multi(const TFrameDev* T, 
       }
       const int cnt = fr.vec ? 4 : 1;
       HotCounts h{0u, 0u, 0u};
-      for (int u = 0; u < 4; u++) {
-        int e;
-        hist_add_hot(h, shared, bins(f, wave_id()), kResPriv, (uint32_t)symbol_of(rv[u], &e),
-                     mine && u < cnt);
-      }
+      for (int u = 0; u < 4; u++)
+        hist_add_hot(h, shared, bins(f, wave_id()), kResPriv, rv[u], mine && u < cnt);
       hist_flush_hot(h, bins(f, wave_id()));
     }
   }

@@ -61,6 +61,12 @@ __device__ inline int symbol_of(uint64_t v, int* extra) {
 // float and reinterpret it for int32 plans).
 constexpr int kDtypeF32 = 0, kDtypeI32 = 1;
 
+// Four floats read with one 16-byte load from any 4-byte aligned address: CDNA
+// global loads of four dwords need dword alignment only (the compiler emits
+// global_load_dwordx4 for this type), so a run of four consecutive inputs is
+// one load wherever it starts.
+typedef float float4_a4 __attribute__((ext_vector_type(4), aligned(4)));
+
 // Value of an input word, exact in double for both types.
 __device__ inline double word_value(float w, int is_int) {
   return is_int ? (double)__float_as_int(w) : (double)w;
@@ -160,21 +166,38 @@ __device__ inline void wave_hist_add(uint32_t* shared, uint32_t* priv, int n_pri
   else if (valid && sym != s0) atomicAdd(&bins[sym], 1u);
 }
 
-// A temporally coded frame's residual symbols are nearly all 0, 1 and 2 (the
-// residuals 0, -1 and +1 after zigzag).  The wave counts those three with one
-// ballot each into wave-uniform counters, which stay in scalar registers and
-// reach the bins once per array and frame (hist_flush_hot); the other symbols
-// go through wave_hist_add.  The private bins must hold symbols 0..2.
+// A temporally coded frame's residuals are nearly all 0, 1 and 2 after zigzag
+// (0, -1 and +1), values that are their own symbols.  The wave counts those
+// three with one ballot each into wave-uniform counters, which stay in scalar
+// registers and reach the bins once per array and frame (hist_flush_hot);
+// only when some lane holds a larger value is its symbol formed and counted
+// through wave_hist_add.  The private bins must hold symbols 0..2.
 struct HotCounts {
   uint32_t c0, c1, c2;
 };
 __device__ inline void hist_add_hot(HotCounts& h, uint32_t* shared, uint32_t* priv, int n_priv,
-                                    uint32_t sym, bool valid) {
+                                    uint32_t v, bool valid) {
   // the bool ballot takes the compare mask as it is (no 0/1 round trip)
-  h.c0 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(valid && sym == 0u));
-  h.c1 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(valid && sym == 1u));
-  h.c2 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(valid && sym == 2u));
-  wave_hist_add(shared, priv, n_priv, sym, valid && sym > 2u);
+  h.c0 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(valid && v == 0u));
+  h.c1 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(valid && v == 1u));
+  h.c2 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(valid && v == 2u));
+  const bool rest = valid && v > 2u;
+  if (__builtin_amdgcn_ballot_w64(rest)) {
+    int e;
+    wave_hist_add(shared, priv, n_priv, (uint32_t)symbol_of(v, &e), rest);
+  }
+}
+// The largest value a wave counted, given each lane's own largest (0 for a lane
+// without values): read off the hot counts unless some lane holds a value
+// above 2, which alone costs a butterfly reduction.  Every lane of the wave
+// must be active.
+__device__ inline uint32_t wave_max_hot(const HotCounts& h, uint32_t m_lane) {
+  if (__builtin_amdgcn_ballot_w64(m_lane > 2u)) {
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) m_lane = max(m_lane, (uint32_t)__shfl_xor((int)m_lane, d, kWave));
+    return m_lane;
+  }
+  return h.c2 ? 2u : (h.c1 ? 1u : 0u);
 }
 __device__ inline void hist_flush_hot(const HotCounts& h, uint32_t* priv) {
   // one lane adds them: the first active one (a grid-stride loop's last
