@@ -1344,6 +1344,19 @@ __global__ __launch_bounds__(kThreads) void k_t_recon(const int32_t* q_ref, int 
 constexpr int kChainGroup = 8;  // frames of a chain whose residuals load together
 typedef float F4 __attribute__((ext_vector_type(4)));
 
+// A residual read as an int32 word (an escape, or a frame without byte
+// residuals) outside +-2^25 cannot come from a valid record (codes and steps
+// keep |s r| below 2^24): it is flagged and taken as 0, so the 32-bit code
+// arithmetic below cannot overflow.
+__device__ inline int32_t checked_residual(int32_t r, uint32_t* bad) {
+  if ((uint32_t)(r + (1 << 25)) >= (1u << 26)) {
+    *bad = 1;
+    return 0;
+  }
+  return r;
+}
+
+template <int DT>
 __global__ __launch_bounds__(kThreads) void k_t_recon_chain(const int32_t* q_ref, int F,
                                                             uint64_t n, GridDev g, ChainOut out,
                                                             int J, int32_t* q_last, uint32_t* err,
@@ -1355,18 +1368,18 @@ __global__ __launch_bounds__(kThreads) void k_t_recon_chain(const int32_t* q_ref
     for (uint64_t s4 = gid; s4 < n / 4; s4 += stride) {
       for (int f = 0; f < F; f++) {
         const int4 qr = reinterpret_cast<const int4*>(q_ref + (uint64_t)f * n)[s4];
-        int64_t q[4] = {qr.x, qr.y, qr.z, qr.w};
-        // one frame of the chain: rr holds its four residuals
+        int32_t q[4] = {qr.x, qr.y, qr.z, qr.w};
+        // one frame of the chain: rr holds its four residuals (|rr| < 2^25)
         auto step = [&](int j, const int32_t* rr) {
           float v[4];
 #pragma unroll
           for (int u = 0; u < 4; u++) {
-            q[u] += (int64_t)g.scale * rr[u];
-            if (q[u] < -(int64_t)kQLimit || q[u] >= (int64_t)kQLimit) {
+            q[u] += g.scale * rr[u];
+            if (q[u] < -kQLimit || q[u] >= kQLimit) {
               bad = 1;
               q[u] = 0;
             }
-            v[u] = reconstruct(q[u], g.eb_q[f], g.m[f], g.dtype);
+            v[u] = reconstruct(q[u], g.eb_q[f], g.m[f], DT);
           }
           // written once and not read again here: a streaming (non-temporal) store
           const F4 vv = {v[0], v[1], v[2], v[3]};
@@ -1411,44 +1424,43 @@ __global__ __launch_bounds__(kThreads) void k_t_recon_chain(const int32_t* q_ref
 #pragma unroll
                 for (int u = 0; u < 4; u++) {
                   rr[u] = (int32_t)(int8_t)(uint8_t)(b >> (8 * u));
-                  if (rr[u] == -128) rr[u] = o[u];  // escaped: the int32 residual
+                  if (rr[u] == -128) rr[u] = checked_residual(o[u], &bad);  // escaped: the int32 residual
                 }
               } else {
                 const int4 r = *reinterpret_cast<const int4*>(o);
-                rr[0] = r.x;
-                rr[1] = r.y;
-                rr[2] = r.z;
-                rr[3] = r.w;
+                rr[0] = checked_residual(r.x, &bad);
+                rr[1] = checked_residual(r.y, &bad);
+                rr[2] = checked_residual(r.z, &bad);
+                rr[3] = checked_residual(r.w, &bad);
               }
               step(j, rr);
             }
           }
         }
         if (q_last)
-          reinterpret_cast<int4*>(q_last + (uint64_t)f * n)[s4] =
-              make_int4((int)q[0], (int)q[1], (int)q[2], (int)q[3]);
+          reinterpret_cast<int4*>(q_last + (uint64_t)f * n)[s4] = make_int4(q[0], q[1], q[2], q[3]);
       }
     }
   } else {
     for (uint64_t s = gid; s < n; s += stride) {
       for (int f = 0; f < F; f++) {
-        int64_t q = q_ref[(uint64_t)f * n + s];
+        int32_t q = q_ref[(uint64_t)f * n + s];
         for (int j = 0; j < J; j++) {
           int32_t r;
           if (out.r8[j][f]) {
             r = out.r8[j][f][s];
-            if (r == -128) r = reinterpret_cast<const int32_t*>(out.p[j][f])[s];
+            if (r == -128) r = checked_residual(reinterpret_cast<const int32_t*>(out.p[j][f])[s], &bad);
           } else {
-            r = reinterpret_cast<const int32_t*>(out.p[j][f])[s];
+            r = checked_residual(reinterpret_cast<const int32_t*>(out.p[j][f])[s], &bad);
           }
-          q += (int64_t)g.scale * r;
-          if (q < -(int64_t)kQLimit || q >= (int64_t)kQLimit) {
+          q += g.scale * r;
+          if (q < -kQLimit || q >= kQLimit) {
             bad = 1;
             q = 0;
           }
-          out.p[j][f][s] = reconstruct(q, g.eb_q[f], g.m[f], g.dtype);
+          out.p[j][f][s] = reconstruct(q, g.eb_q[f], g.m[f], DT);
         }
-        if (q_last) q_last[(uint64_t)f * n + s] = (int32_t)q;
+        if (q_last) q_last[(uint64_t)f * n + s] = q;
       }
     }
   }
@@ -1818,8 +1830,10 @@ void launch_t_recon_chain(const int32_t* q_ref, int F, uint64_t n, const GridDev
       vec = vec && al16(out.p[j][f]) && (reinterpret_cast<uintptr_t>(out.r8[j][f]) & 3) == 0;
       per += out.r8[j][f] ? 5 : 8;
     }
-  launch_timed("t_recon", n * (per + 4ull * F + (q_last ? 4ull * F : 0)), k_t_recon_chain, grid_for(vec ? n / 4 : n, kThreads * 2, 1u << 16), kThreads, 0, s,
-               q_ref, F, n, g, out, J, q_last, err, vec);
+  auto* kernel = g.dtype == kDtypeI32 ? k_t_recon_chain<kDtypeI32> : k_t_recon_chain<kDtypeF32>;
+  launch_timed("t_recon", n * (per + 4ull * F + (q_last ? 4ull * F : 0)), kernel,
+               grid_for(vec ? n / 4 : n, kThreads * 2, 1u << 16), kThreads, 0, s, q_ref, F, n, g,
+               out, J, q_last, err, vec);
 }
 
 void launch_scatter_records(const unsigned long long* offs, const uint8_t* src, const uint64_t* tab,
