@@ -498,6 +498,134 @@ def bench_served(args, torch, lcp, datagen, dev):
     }
 
 
+def bench_next_rows(args, torch, lcp, frames, k, steps=2, n_random=16):
+    """The next rows built beyond the hot path, on the trajectory's resident frames:
+    int32 fields (the frames as fixed point, 1e-3 lattice units), data of two
+    spatial dimensions (x and y), and the random-access container (Sec. 7.3) of the
+    float stream's records.  Each leg checks its output before reporting."""
+    res = {}
+    n, nf = frames[0].shape[1], len(frames)
+    dev = frames[0].device
+    kw = dict(multi_frame=True, batch_size=args.batch, block_log2=k, max_particles=n)
+
+    def timed(plan, dplan, xs, outbuf, decs, timer=None):
+        """One untimed pass, then `steps` timed ones (the kernel timer, if named, over those)."""
+        tc = td = 0.0
+        for rep in range(steps + 1):
+            if rep == 1 and timer:
+                plan.timer_set(timer)
+            plan.reset()
+            dplan.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out, offs, used, _ = plan.compress(xs, out=outbuf)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            dplan.decompress(out, offs, outs=decs)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if rep:
+                tc += t1 - t0
+                td += t2 - t1
+        return tc / steps, td / steps, out, offs, used
+
+    # int32 fields: the trajectory in fixed point (rounded to nearest), relative bound as the
+    # float leg's; the run kernel's integer instance timed
+    ints = [(f.double() * 1000.0).round().to(torch.int32) for f in frames]
+    plan = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, dtype=lcp.DTYPE_I32, **kw)
+    dplan = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, dtype=lcp.DTYPE_I32, **kw)
+    cap = sum((plan.bound(n) + 3) & ~3 for _ in ints)
+    outbuf = torch.empty(cap, dtype=torch.uint8, device=dev)
+    decs = [torch.empty((3, n), dtype=torch.int32, device=dev) for _ in ints]
+    tc, td, out, offs, used = timed(plan, dplan, ints, outbuf, decs, "t_resid_run/1")
+    kms, kl, kb = plan.timer_read()
+    eb_i = args.eb * float(int(ints[0].max()) - int(ints[0].min()))
+    chk = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, dtype=lcp.DTYPE_I32, **kw)
+    o2, of2, _, perms = chk.compress(ints[:3], want_perm=True)
+    dchk = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, dtype=lcp.DTYPE_I32, **kw)
+    d2 = dchk.decompress(o2, of2)
+    err = max(int((d2[j].long() - ints[j][:, perms[j].long()].long()).abs().max()) for j in range(3))
+    assert err <= eb_i, (err, eb_i)
+    size_i = sum(x.numel() * 4 for x in ints)
+    achieved = kb / (kms * 1e-3) / 1e9 if kl else None
+    res["int32"] = {
+        "workload": f"the trajectory's {nf} frames as int32 fixed point (1e-3 lattice units), "
+                    f"eb={args.eb:g} x range, batch {args.batch}, LCP-FSM S/T",
+        "compress_GBps": size_i / tc / 1e9, "decompress_GBps": size_i / td / 1e9,
+        "GBps": size_i / (tc + td) / 1e9, "ratio": size_i / offs[-1],
+        "temporal_frames": sum(1 for u in used if u == lcp.METHOD_T),
+        "max_abs_err": err, "eb_abs": eb_i,
+        "run_kernel": {"launches": kl, "avg_launch_us": kms / kl * 1e3 if kl else None,
+                       "achieved_GBps": achieved,
+                       "frac": achieved / HBM_PEAK_GBPS if achieved else None}}
+    del ints, plan, dplan, chk, dchk, outbuf, decs, o2, d2
+    torch.cuda.empty_cache()
+
+    # two spatial dimensions: x and y of every frame
+    xy = [f[:2] for f in frames]
+    plan = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, n_fields=2, n_dims=2, **kw)
+    dplan = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, n_fields=2, n_dims=2, **kw)
+    cap = sum((plan.bound(n) + 3) & ~3 for _ in xy)
+    outbuf = torch.empty(cap, dtype=torch.uint8, device=dev)
+    decs = [torch.empty((2, n), dtype=torch.float32, device=dev) for _ in xy]
+    tc, td, out, offs, used = timed(plan, dplan, xy, outbuf, decs)
+    size_2 = sum(x.numel() * 4 for x in xy)
+    res["two_dims"] = {
+        "workload": f"x and y of the trajectory's {nf} frames (n_dims = 2), eb={args.eb:g} x range",
+        "compress_GBps": size_2 / tc / 1e9, "decompress_GBps": size_2 / td / 1e9,
+        "GBps": size_2 / (tc + td) / 1e9, "ratio": size_2 / offs[-1],
+        "temporal_frames": sum(1 for u in used if u == lcp.METHOD_T)}
+    del plan, dplan, outbuf, decs
+    torch.cuda.empty_cache()
+
+    # the container: the float stream's records packed; one sequential retrieval of every
+    # frame, then single-frame requests in random order, each checked against the
+    # sequential decode
+    plan = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, **kw)
+    dplan = lcp.Plan(args.eb, lcp.EB_REL_GLOBAL, **kw)
+    out, offs, _, _ = plan.compress(frames)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cbuf = lcp.Container.pack(out, offs, args.batch)
+    torch.cuda.synchronize()
+    t_pack = time.perf_counter() - t0
+    cont = lcp.Container(cbuf)
+    seq = [torch.empty((3, n), dtype=torch.float32, device=dev) for _ in range(nf)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    dec_all = cont.retrieve(dplan, list(range(nf)), seq)
+    torch.cuda.synchronize()
+    t_all = time.perf_counter() - t0
+    rng = np.random.default_rng(7)
+    picks = [int(v) for v in rng.integers(0, nf, size=n_random)]
+    one = torch.empty((3, n), dtype=torch.float32, device=dev)
+    lat, decoded = [], []
+    for fidx in picks:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        decoded.append(cont.retrieve(dplan, [fidx], [one]))
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - t0)
+        assert torch.equal(one.view(torch.int32), seq[fidx].view(torch.int32)), fidx
+    size_d = sum(f.numel() * 4 for f in frames)
+    res["container"] = {
+        "workload": f"the float trajectory's {nf} records (batch {args.batch}) packed for "
+                    f"random access",
+        "frames": nf, "anchors": cont.anchors, "container_bytes": cbuf.numel(),
+        "pack_ms": t_pack * 1e3,
+        "retrieve_all_GBps": size_d / t_all / 1e9, "retrieve_all_records_decoded": dec_all,
+        "single_frame_requests": n_random,
+        "single_frame_ms_p50": float(np.percentile(np.array(lat) * 1e3, 50)),
+        "single_frame_ms_max": float(np.max(lat) * 1e3),
+        "records_decoded_per_request_mean": float(np.mean(decoded)),
+        "records_decoded_per_request_max": int(np.max(decoded)),
+        "checked": "every single-frame request equals the sequential retrieval bit for bit"}
+    cont.close()
+    del plan, dplan, out, cbuf, seq, one
+    torch.cuda.empty_cache()
+    return res
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch from the committed counter summary, if it was taken on
     the current kernel sources (else None)."""
@@ -527,9 +655,10 @@ def main():
     ap.add_argument("--roofline-kernel", default=ROOFLINE_KERNEL)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run three 256 MiB device copies (counter calibration)")
-    ap.add_argument("--workloads", default="md,c1,c3,batched,served",
-                    help="comma list: md (the trajectory, the headline value), c1 (uniform "
-                         "frame), c3 (cosmology snapshot), batched, served")
+    ap.add_argument("--workloads", default="md,next,c1,c3,batched,served",
+                    help="comma list: md (the trajectory, the headline value), next (int32 "
+                         "fields, two dimensions and the container on the trajectory's frames; "
+                         "needs md), c1 (uniform frame), c3 (cosmology snapshot), batched, served")
     ap.add_argument("--c3-n", type=int, default=1 << 27)
     ap.add_argument("--c3-steps", type=int, default=3)
     ap.add_argument("--c3-timer", default="radix_scatter")
@@ -714,6 +843,10 @@ def main():
             "max_abs_err": err5, "note": "one untimed-warmup-free pass; every 7th frame checked"}
         log(f"anchor scale 5: ratio {size_d / offs5[-1]:.3f} (without {ratio:.3f})")
         del splan, sdplan, dec5, out5, perms5
+        if "next" in work:
+            log("int32 fields, two dimensions, container")
+            result["next_rows"] = bench_next_rows(args, torch, lcp, frames, k)
+            log(json.dumps(result["next_rows"]))
         if not args.no_cpu_baseline:
             log(f"cpu baseline: oracle on {len(frames_np)} frames")
             cb = cpu_baseline(frames_np, args.eb, args.batch, k, list(used), 12 * args.n)
