@@ -8,7 +8,8 @@ int32 range (the saturating reconstruction), multi-frame streams one call
 (temporal runs) and frame by frame, anchors with an error-bound scale and the
 fallback when an integer bin cannot be split, a 2-D stream with a
 supplementary field, served streams of both element types merged into shared
-launches, the entry point without allocation, and the refusals (a range past
+launches, the entry point without allocation, the container of int32 records
+(packed bytes and retrievals in several orders), and the refusals (a range past
 the code limit, a record of the other type).
 """
 from __future__ import annotations
@@ -251,3 +252,31 @@ def test_frame_2p20(lcp):
         rec, u, _ = ost.compress(x)
         assert used[t] == u, t
         assert out[offs[t]:offs[t + 1]].cpu().numpy().tobytes() == rec, t
+
+
+def test_container_of_int_records(lcp):
+    """int32 records packed for random access: the bytes, and every retrieval
+    (frames in any order), equal the oracle's."""
+    n, batch = 20003, 4
+    xs = md_ints(n, frames=14, seed=23, step=0.004)
+    kw = dict(multi_frame=True, batch_size=batch, block_log2=4, max_particles=n,
+              dtype=lcp.DTYPE_I32)
+    plan = lcp.Plan(4.0, lcp.EB_ABS, **kw)
+    out, offs, _, _ = plan.compress([dev(x) for x in xs])
+    recs = [out[offs[j]:offs[j + 1]].cpu().numpy().tobytes() for j in range(len(xs))]
+    want = O.container_pack(recs, batch)
+    cont = lcp.Container.pack(out, offs, batch)
+    assert cont.cpu().numpy().tobytes() == want
+    C = lcp.Container(cont)
+    dplan = lcp.Plan(4.0, lcp.EB_ABS, **kw)
+    for req in ([13], [2, 9, 5, 6], list(range(14))[::-1]):
+        outs = [torch.empty((3, n), dtype=torch.int32, device="cuda") for _ in req]
+        decoded = C.retrieve(dplan, req, outs)
+        wout, wdec = O.container_retrieve(want, req, O.EB_ABS, 4.0, block_log2=4,
+                                          dtype=O.DTYPE_I32)
+        assert decoded == wdec
+        for k, o in zip(req, outs):
+            got = o.cpu().numpy()
+            for f in range(3):
+                assert np.array_equal(got[f], wout[k][f]), (k, f)
+    C.close()
