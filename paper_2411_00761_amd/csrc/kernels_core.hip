@@ -429,7 +429,7 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
 // v8 + a * astride, escapes at vesc + a * astride, histogram copies
 // [a copies, (a + 1) copies), work record zw[a]; frame j's error word at
 // err + j * err_stride.
-constexpr int kRunPriv = 128;
+constexpr int kRunPriv = 64;
 template <int F, int DT>
 __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, uint64_t n,
                                                           GridDev g, const uint32_t* perm,

@@ -1993,7 +1993,7 @@ lcp_status alloc_state(lcp_plan_s* P) {
 // Frames a temporal run of a multi-frame plan codes at once: as many as keep
 // the run's buffers (residual bytes, escapes, staging, histogram copies) within
 // kRunBytes, at most kRunMax; fewer than two means no runs.
-constexpr uint64_t kRunBytes = 2ull << 30;
+constexpr uint64_t kRunBytes = 4ull << 30;
 int run_frames_for(const lcp_plan_s* P) {
   if (!P->p.multi_frame) return 0;
   const uint64_t N = P->N, F = (uint64_t)P->F;

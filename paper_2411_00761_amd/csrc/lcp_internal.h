@@ -305,7 +305,7 @@ void launch_t_resid(const FieldPtrs& x, int F, uint64_t n, const GridDev& g,
                     unsigned long long* hist_max, ArrWork* zero_words, hipStream_t s);
 // A temporal run: up to kRunMax frames coded as a chain on one reference grid
 // and slot order in one launch (frame j's fields fr.x[j]); see k_t_resid_run.
-constexpr int kRunMax = 16;
+constexpr int kRunMax = 32;
 // Frames one run launch can take at F fields (kRunMax, or fewer for wide F).
 int run_launch_frames(int F);
 struct RunFrames {
