@@ -677,8 +677,9 @@ def main():
     work = args.workloads.split(",")
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print(json.dumps({"error": "this build measures one GPU only; run with --gpus 1 "
-                                   "(multi-GPU sharding is a design note in DESIGN.md)"}))
+        print(json.dumps({"error": "bench.py measures one GPU: run with --gpus 1 (whole "
+                                   "batches of frames would shard across GPUs; that path is "
+                                   "not implemented)"}))
         sys.exit(2)
 
     import torch
@@ -752,7 +753,8 @@ def main():
         comp_bytes = offs[-1]
         ratio = size_d / comp_bytes
         n_t = sum(1 for u in used if u == lcp.METHOD_T)
-        # algorithmic bytes of one step by Sec. 8(d)'s rules, per frame by its method
+        # algorithmic bytes of one step, per frame by its method: spatial 4FN + C both ways,
+        # temporal 12FN + 4N + C to compress and 12FN + C to decompress
         bc = bd = 0
         for j, u in enumerate(used):
             c = offs[j + 1] - offs[j]

@@ -20,8 +20,8 @@
  *                               temporally correlated)
  *   block-size search ......... Sec. 7.4.1 (candidates 2^k, 0<=k<=16, on a sample)
  * The readings taken where the paper is silent (rounding margin, modular deltas,
- * escape classes, length limit, chunking, record layout, FSM details) are listed
- * in the design doc; each is restated where it is used below.
+ * escape classes, length limit, chunking, record layout, FSM details) are each
+ * stated where they are used below.
  *
  * Build: gcc -O2 -ffp-contract=off -fno-fast-math -shared -fPIC.  No contraction,
  * so every double/float operation is one IEEE operation in round-to-nearest.

@@ -9,8 +9,9 @@
  * HIP implementation under paper_2411_00761_amd/.
  *
  * Every entry point works on host memory and returns an lco status code.
- * The byte format it writes is the frame record described in the design doc
- * ("Frame record format"); the oracle is the executable definition of it.
+ * The byte format it writes is the frame record (an 80-byte header, one 8-byte
+ * grid slot per field, a 32-byte directory entry per coded array, then the
+ * arrays); the oracle's write_record is the executable definition of it.
  */
 #ifndef LCP_ORACLE_H
 #define LCP_ORACLE_H

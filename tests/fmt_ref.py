@@ -1,7 +1,7 @@
 """Independent pure-Python reader of the LCP frame record (test helper).
 
-Written from the record layout stated in DESIGN.md ("Frame record format"), not
-from either implementation, so that a record written by the C oracle or by the GPU
+Written from the record layout itself (header fields, grid slots, array
+directory, fixed-length and chunked Huffman arrays), not from either implementation, so that a record written by the C oracle or by the GPU
 library can be taken apart and checked field by field.  Slow: small inputs only.
 """
 from __future__ import annotations
