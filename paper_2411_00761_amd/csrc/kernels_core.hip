@@ -242,17 +242,18 @@ __global__ __launch_bounds__(kThreads) void k_scan_apply4(ScanSet a, uint64_t n,
 
 // LCP-T: the frame's codes on the reference grid, in the reference's slot order,
 // minus the reference codes (zigzag); the new codes become the next reference.
-// The frame must stay inside the grid's float32 margin (|x| + 2 eb < 2^E) and
-// code range (|2q+1| < 2^24); a particle outside it flags the frame.
-// int32 grids have no margin to keep (eb2 = 0, lim = infinity): their
-// reconstructions are exact integers.
+// The frame must stay inside the grid's float32 margin (|x| + 2 eb < 2^E,
+// evaluated in double: since that sum grows with |x|, it holds exactly for
+// |x| <= xmax, the largest float for which it holds, found on the host) and
+// code range (|2q+1| < 2^24); a particle outside it flags the frame.  int32
+// grids have no margin to keep: their reconstructions are exact integers.
 // is_int: the grid's type, a constant where the caller is specialised for it.
 // The checks are selects, not branches.
 __device__ inline void t_code_as(float xv, int is_int, const GridDev& g, int f, uint32_t* bad,
                                  int32_t* qo) {
   const double xd = word_value(xv, is_int);
   const bool finite = is_int || __builtin_isfinite(xv);
-  const bool inside = fabs(xd) + g.eb2[f] < g.lim[f];
+  const bool inside = is_int || fabsf(xv) <= g.xmax[f];
   *bad |= (finite ? 0u : (uint32_t)kErrNonFinite) | (finite && !inside ? (uint32_t)kErrRange : 0u);
   int32_t q = quantise(xd, g.md[f], g.inv[f]);
   if (q < -kQLimit || q >= kQLimit) {

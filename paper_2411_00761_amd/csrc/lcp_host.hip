@@ -875,14 +875,37 @@ lcp_status extent(lcp_plan_s* P, const float* const* x, uint64_t n, double* lo, 
 // LCP-T on one frame against a resident reference.  Whether the frame fits the
 // reference grid (finite values, float32 margin, code range) is checked by the
 // residual kernel itself, so no extent pass is needed.
+// The largest float32 x >= 0 with x + eb2 < lim in double arithmetic (the
+// temporal frames' margin test of a float32 grid; -1 when no x passes).  The
+// double sum is monotone in x, so the floats that pass are one interval from
+// 0, and a bisection over the float bit patterns (ordered as integers for
+// x >= 0) finds its end with the same IEEE double addition the test uses.
+float margin_xmax(double eb2, double lim) {
+  auto ok = [&](uint32_t bits) {
+    float x;
+    memcpy(&x, &bits, 4);
+    return (double)x + eb2 < lim;
+  };
+  if (!ok(0u)) return -1.0f;
+  uint32_t lo = 0u, hi = 0x7F800000u;  // ok(lo); hi (infinity) fails
+  while (hi - lo > 1u) {
+    const uint32_t mid = lo + (hi - lo) / 2u;
+    if (ok(mid)) lo = mid;
+    else hi = mid;
+  }
+  float x;
+  memcpy(&x, &lo, 4);
+  return x;
+}
+
 GridDev t_grid(const RefState& ref, int F) {
   GridDev gd = to_dev(ref.grid, F);
   gd.scale = ref.scale;
   for (int f = 0; f < F; f++) {
     // int32 grids: exact integer reconstructions, no float32 margin to keep
-    const bool is_int = ref.grid[f].dtype == kDtypeI32;
-    gd.eb2[f] = is_int ? 0.0 : 2.0 * ref.grid[f].eb;
-    gd.lim[f] = is_int ? HUGE_VAL : ldexp(1.0, ref.grid[f].E);
+    const HostGrid& hg = ref.grid[f];
+    gd.xmax[f] = hg.dtype == kDtypeI32 ? HUGE_VALF
+                                       : margin_xmax(2.0 * hg.eb, ldexp(1.0, hg.E));
   }
   return gd;
 }

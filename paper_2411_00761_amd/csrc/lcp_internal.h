@@ -26,8 +26,9 @@ struct GridDev {
   float eb_q[kMaxF];
   double md[kMaxF];   // quantisation origin (see quantise)
   double inv[kMaxF];
-  double eb2[kMaxF];  // 2 * the user's bound (temporal feasibility check)
-  double lim[kMaxF];  // 2^E: |x| + 2 eb must stay below it on this grid
+  // temporal frames on a float32 grid: the largest |x| whose value keeps the
+  // grid's rounding margin (|x| + 2 eb < 2^E in double arithmetic)
+  float xmax[kMaxF];
   // temporal frames: the step of the codes on this grid (1, or the scale of
   // the anchor the grid was made for, Sec. 7.4.2)
   int32_t scale;
