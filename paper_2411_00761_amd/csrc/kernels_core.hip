@@ -365,7 +365,7 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
         HotCounts h{0u, 0u, 0u};
 #pragma unroll
         for (int j = 0; j < 4; j++) count(f, h, rv[j]);
-        hist_flush_hot(h, bins(f, wave_id()));
+        hist_flush_hot(h, bins(f, wave_id()), 4u * (uint32_t)__popcll(__ballot(1)));
       }
     }
   } else {
@@ -386,7 +386,7 @@ __global__ __launch_bounds__(kThreads) void k_t_resid(FieldPtrs x, int F, uint64
         rmax[f] = max(rmax[f], r);
         HotCounts h{0u, 0u, 0u};
         count(f, h, r);
-        hist_flush_hot(h, bins(f, wave_id()));
+        hist_flush_hot(h, bins(f, wave_id()), (uint32_t)__popcll(__ballot(1)));
       }
     }
   }
@@ -490,8 +490,15 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
     }
   }
   // vector path: the next frame's values are requested while this frame is
-  // coded (software pipelining: twice the loads in flight per wave)
+  // coded (software pipelining: twice the loads in flight per wave).  A lane
+  // without slots keeps zeros: it codes them like the others, and nothing of
+  // it is stored or counted
   float xn[F][4];
+#pragma unroll
+  for (int f = 0; f < F; f++) xn[f][0] = xn[f][1] = xn[f][2] = xn[f][3] = 0.0f;
+  // the values each array of a frame counts: four per lane with slots (one on
+  // the scalar path)
+  const uint32_t n_valid = (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(mine)) * (vec ? 4u : 1u);
   auto load_frame = [&](int j) {
 #pragma unroll
     for (int f = 0; f < F; f++) {
@@ -530,14 +537,15 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
       HotCounts h{0u, 0u, 0u};
       if (vec) {
         const float* xv = xc[f];
-        uint32_t rv[4];
+        uint32_t rv[4], fl = 0;
 #pragma unroll
         for (int u = 0; u < 4; u++) {
-          int32_t qc = 0, qn = 0;
-          if (mine) t_code_as(xv[u], DT, g, f, &bad, &qc);
-          rv[u] = (uint32_t)zigzag32(t_step(qc, q[f][u], g.scale, &bad, &qn));
+          int32_t qc, qn;
+          t_code_as(xv[u], DT, g, f, &fl, &qc);
+          rv[u] = (uint32_t)zigzag32(t_step(qc, q[f][u], g.scale, &fl, &qn));
           q[f][u] = (int32_t)qn;
         }
+        bad |= mine ? fl : 0u;
         if (mine) {
           rmax = max(max(rv[0], rv[1]), max(rv[2], rv[3]));
           uint32_t bytes = 0;
@@ -565,7 +573,7 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_run(RunFrames fr, int J, u
         }
         hist_add_hot(h, shared, bins, kRunPriv, r, mine);
       }
-      hist_flush_hot(h, bins);
+      hist_flush_hot(h, bins, n_valid);
       const uint32_t wmax = wave_max_hot(h, rmax);
       if (lane_id() == 0 && wmax) atomicMax(&smax[j][f], wmax);
     }
@@ -731,7 +739,8 @@ __global__ __launch_bounds__(kThreads) void k_t_resid_multi(const TFrameDev* T, 
       HotCounts h{0u, 0u, 0u};
       for (int u = 0; u < 4; u++)
         hist_add_hot(h, shared, bins(f, wave_id()), kResPriv, rv[u], mine && u < cnt);
-      hist_flush_hot(h, bins(f, wave_id()));
+      hist_flush_hot(h, bins(f, wave_id()),
+                     (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(mine)) * (uint32_t)cnt);
     }
   }
   if (cur >= 0) flush(cur);

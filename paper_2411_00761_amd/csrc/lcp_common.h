@@ -167,22 +167,25 @@ __device__ inline void wave_hist_add(uint32_t* shared, uint32_t* priv, int n_pri
 }
 
 // A temporally coded frame's residuals are nearly all 0, 1 and 2 after zigzag
-// (0, -1 and +1), values that are their own symbols.  The wave counts those
-// three with one ballot each into wave-uniform counters, which stay in scalar
-// registers and reach the bins once per array and frame (hist_flush_hot);
-// only when some lane holds a larger value is its symbol formed and counted
-// through wave_hist_add.  The private bins must hold symbols 0..2.
+// (0, -1 and +1), values that are their own symbols.  The wave counts 1, 2 and
+// the rest with one ballot each into wave-uniform counters, which stay in
+// scalar registers; the zeros are what remains of the values the caller knows
+// it counted, and all three reach the bins once per array and frame
+// (hist_flush_hot).  Only when some lane holds a value above 2 is its symbol
+// formed and counted through wave_hist_add.  The private bins must hold
+// symbols 0..2.
 struct HotCounts {
-  uint32_t c0, c1, c2;
+  uint32_t c1, c2, rest;
 };
 __device__ inline void hist_add_hot(HotCounts& h, uint32_t* shared, uint32_t* priv, int n_priv,
                                     uint32_t v, bool valid) {
   // the bool ballot takes the compare mask as it is (no 0/1 round trip)
-  h.c0 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(valid && v == 0u));
   h.c1 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(valid && v == 1u));
   h.c2 += (uint32_t)__popcll(__builtin_amdgcn_ballot_w64(valid && v == 2u));
   const bool rest = valid && v > 2u;
-  if (__builtin_amdgcn_ballot_w64(rest)) {
+  const uint64_t rm = __builtin_amdgcn_ballot_w64(rest);
+  if (rm) {
+    h.rest += (uint32_t)__popcll(rm);
     int e;
     wave_hist_add(shared, priv, n_priv, (uint32_t)symbol_of(v, &e), rest);
   }
@@ -199,11 +202,13 @@ __device__ inline uint32_t wave_max_hot(const HotCounts& h, uint32_t m_lane) {
   }
   return h.c2 ? 2u : (h.c1 ? 1u : 0u);
 }
-__device__ inline void hist_flush_hot(const HotCounts& h, uint32_t* priv) {
+// n_valid: the values the wave passed as valid since the counters started.
+__device__ inline void hist_flush_hot(const HotCounts& h, uint32_t* priv, uint32_t n_valid) {
+  const uint32_t c0 = n_valid - h.c1 - h.c2 - h.rest;
   // one lane adds them: the first active one (a grid-stride loop's last
   // iteration may have left out the low lanes)
   if (lane_id() == __ffsll((long long)__ballot(1)) - 1) {
-    if (h.c0) atomicAdd(&priv[0], h.c0);
+    if (c0) atomicAdd(&priv[0], c0);
     if (h.c1) atomicAdd(&priv[1], h.c1);
     if (h.c2) atomicAdd(&priv[2], h.c2);
   }
