@@ -787,6 +787,12 @@ def main():
             del src, dst
 
         achieved = (kbytes / klaunch) / (kms / klaunch * 1e-3) / 1e9 if klaunch else None
+        # what the run kernel itself reads and writes per launch: J (4F + F) + 4 + 8F bytes
+        # per particle (J frames read and their residual bytes written; the permutation and
+        # the first reference codes read and the last codes written once), F = 3
+        own = ((kbytes / klaunch) / (4 + 12 * 3) * (5 * 3) + args.n * (4 + 8 * 3)) if klaunch \
+            else None
+        own_gbps = own / (kms / klaunch * 1e-3) / 1e9 if klaunch else None
         result.update({
             "value": size_d * args.steps / (tc + td) / 1e9,
             "ms_per_step": t_total / args.steps * 1e3,
@@ -808,12 +814,18 @@ def main():
                          "traffic": measured_traffic(args.roofline_kernel),
                          "timed_launches": klaunch, "timed_every": 1,
                          "avg_launch_us": (kms / klaunch * 1e3) if klaunch else None,
+                         "own_bytes_per_launch": own, "own_GBps": own_gbps,
+                         "own_frac": (own_gbps / HBM_PEAK_GBPS) if own_gbps else None,
+                         "own_vs_copy_ceiling": (own_gbps / ceiling["copy_GBps"])
+                         if own_gbps else None,
                          "bytes_per_launch": (kbytes / klaunch) if klaunch else None,
                          "bytes_rule": "4 + 12F per particle and frame (a frame, its reference "
                                        "codes and the slot permutation read, its codes written) "
                                        "times the J frames of the launch; the run kernel keeps "
                                        "the codes in registers and itself moves J(4F + F) + 4 + "
-                                       "8F bytes per particle",
+                                       "8F bytes per particle (own_bytes_per_launch), so frac, "
+                                       "on the per-frame figure, can pass 1 where own_frac "
+                                       "cannot",
                          "copy_ceiling": ceiling, "mall_note": MALL_NOTE},
             "path_roofline": {"bound": "hbm",
                               "compress": path_frac(bc * args.steps, tc),
