@@ -766,7 +766,7 @@ __global__ __launch_bounds__(kThreads) void k_t_recon_multi(const TReconDev* T, 
         bad = 1;
         q = 0;
       }
-      fr.out[f][s] = reconstruct(q, fr.eb_q[f], fr.m[f], fr.dtype);
+      fr.out[f][s] = reconstruct((int32_t)q, fr.eb_q[f], fr.m[f], fr.dtype);
       fr.q_new[(uint64_t)f * n + s] = (int32_t)q;
     }
   }
@@ -1236,7 +1236,7 @@ __global__ __launch_bounds__(kThreads) void k_s_recon_b(const uint32_t* blk, con
         bad = true;
         q = 0;
       }
-      g.out[f][s] = reconstruct((int64_t)q, g.eb_q[f], g.m[f], g.dtype);
+      g.out[f][s] = reconstruct((int32_t)q, g.eb_q[f], g.m[f], g.dtype);
     }
   }
   if (bad) atomicOr(err, kErrCorrupt);
@@ -1294,7 +1294,7 @@ __global__ __launch_bounds__(kThreads) void k_s_recon(const uint32_t* blk, const
         atomicOr(err, kErrCorrupt);
         q = 0;
       }
-      out.p[f][s] = reconstruct((int64_t)q, g.eb_q[f], g.m[f], g.dtype);
+      out.p[f][s] = reconstruct((int32_t)q, g.eb_q[f], g.m[f], g.dtype);
       if (q_slot) q_slot[(uint64_t)f * n + s] = (int32_t)q;
     }
   }
@@ -1322,7 +1322,7 @@ __global__ __launch_bounds__(kThreads) void k_t_recon(const int32_t* q_ref, int 
             bad = 1;
             q[j] = 0;
           }
-          o[j] = reconstruct(q[j], g.eb_q[f], g.m[f], g.dtype);
+          o[j] = reconstruct((int32_t)q[j], g.eb_q[f], g.m[f], g.dtype);
         }
         reinterpret_cast<float4*>(out.p[f])[s4] = make_float4(o[0], o[1], o[2], o[3]);
         if (q_slot)
@@ -1339,7 +1339,7 @@ __global__ __launch_bounds__(kThreads) void k_t_recon(const int32_t* q_ref, int 
           bad = 1;
           q = 0;
         }
-        out.p[f][s] = reconstruct(q, g.eb_q[f], g.m[f], g.dtype);
+        out.p[f][s] = reconstruct((int32_t)q, g.eb_q[f], g.m[f], g.dtype);
         if (q_slot) q_slot[(uint64_t)f * n + s] = (int32_t)q;
       }
     }

@@ -87,14 +87,16 @@ __device__ inline int32_t quantise(double x, double md, double inv) {
   return (int32_t)fmin(fmax(t, -2147483648.0), 2147483647.0);
 }
 
-// Reconstruction as a 4-byte output word.  float32: (2q+1) eb_q + m, one
-// rounding.  int32 (m and eb_q then hold the bits of the origin and of the half
-// width hb): m + q (2 hb + 1) + hb, held to the int32 range, which only moves a
-// value toward its input.
-__device__ inline float reconstruct(int64_t q, float eb_q, float m, int is_int) {
+// Reconstruction as a 4-byte output word from a code within +-2^23 (every
+// caller range-checks it first, so 2q+1 is exact in 32 bits and converts to
+// float in one instruction).  float32: (2q+1) eb_q + m, one rounding.  int32
+// (m and eb_q then hold the bits of the origin and of the half width hb):
+// m + q (2 hb + 1) + hb, held to the int32 range, which only moves a value
+// toward its input.
+__device__ inline float reconstruct(int32_t q, float eb_q, float m, int is_int) {
   if (is_int) {
     const int64_t hb = (int64_t)__float_as_uint(eb_q);
-    int64_t v = (int64_t)__float_as_int(m) + q * (2 * hb + 1) + hb;
+    int64_t v = (int64_t)__float_as_int(m) + (int64_t)q * (2 * hb + 1) + hb;
     v = v > (int64_t)INT32_MAX ? (int64_t)INT32_MAX : v;
     v = v < (int64_t)INT32_MIN ? (int64_t)INT32_MIN : v;
     return __int_as_float((int32_t)v);
