@@ -79,12 +79,18 @@ __device__ inline double word_value(float w, int is_int) {
 // and (d + 1/2) / w lies at least 1 / (2w) from every integer while the two
 // roundings move it by at most 2^-52 (d + 1/2) / w < 2^-19 / w, so the floor
 // is floor(d / w) exactly.
-// The codes in use lie within +-2^23: a value beyond the int32 range (or NaN)
-// is held at its ends, where every caller's range check rejects it, so one
-// saturating 32-bit conversion serves instead of a 64-bit one.
+// The codes in use lie within +-2^23: a value beyond the int32 range is held
+// at its ends (NaN gives 0), where every caller's range check (or its
+// finiteness test) rejects it, so one saturating 32-bit conversion serves
+// instead of a 64-bit one.  The instruction saturates by itself; it is named
+// directly because the language leaves an out-of-range conversion undefined.
+__device__ inline int32_t cvt_i32_sat(double t) {
+  int32_t r;
+  asm("v_cvt_i32_f64 %0, %1" : "=v"(r) : "v"(t));
+  return r;
+}
 __device__ inline int32_t quantise(double x, double md, double inv) {
-  const double t = floor((x - md) * inv);
-  return (int32_t)fmin(fmax(t, -2147483648.0), 2147483647.0);
+  return cvt_i32_sat(floor((x - md) * inv));
 }
 
 // Reconstruction as a 4-byte output word from a code within +-2^23 (every
