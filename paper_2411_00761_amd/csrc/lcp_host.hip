@@ -547,6 +547,10 @@ lcp_status enc_add(lcp_plan_s* P, EncBuild& B, const ArrIn& in, uint64_t nb, int
   return LCP_OK;
 }
 
+constexpr uint64_t kFusedPackBlocks = 4096;  // total packing workgroups of a fused launch
+constexpr uint64_t kFusedCopyBlocks = 4096;  // ... emit workgroups of its Huffman arrays
+constexpr uint64_t kFusedFixedBlocks = 1024;  // ... and of its fixed-length ones (rare)
+
 // The host side of an encode launch set: prefix tables, and the record, array
 // and prefix tables uploaded on stream s unless the device already holds them.
 lcp_status enc_prepare(lcp_plan_s* P, EncBuild& B, EncLaunch* Lo, hipStream_t s) {
@@ -561,6 +565,20 @@ lcp_status enc_prepare(lcp_plan_s* P, EncBuild& B, EncLaunch* Lo, hipStream_t s)
   uint32_t* pc = ph + (NA + 1);
   uint32_t* pf = pc + (NA + 1);
   uint32_t* pk = pf + (NA + 1);
+  // a launch of many arrays whose packing builds each array's code (the
+  // records of a run): fewer workgroups per array, so that what each one does
+  // once (that build, and the emit's sum of the chunk counts before its range)
+  // is shared by more chunks; the grid stays several workgroups per compute unit
+  if (B.fused && NA > 1) {
+    const uint32_t per_pack = (uint32_t)((kFusedPackBlocks + NA - 1) / NA);
+    const uint32_t per_copy = (uint32_t)((kFusedCopyBlocks + NA - 1) / NA);
+    const uint32_t per_fixed = (uint32_t)((kFusedFixedBlocks + NA - 1) / NA);
+    for (int a = 0; a < NA; a++) {
+      if (B.cb[a] > per_pack) B.cb[a] = per_pack;
+      if (B.kb[a] > per_copy) B.kb[a] = per_copy;
+      if (B.fb[a] > per_fixed) B.fb[a] = per_fixed;
+    }
+  }
   uint32_t h = 0, c = 0, f = 0, k = 0;
   for (int a = 0; a < NA; a++) {
     ph[a] = h;
