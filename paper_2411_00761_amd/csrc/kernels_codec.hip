@@ -1668,7 +1668,7 @@ __device__ inline void copy_huff_block(const EncArr* E, const ArrWork* W, uint32
     // word by word
     uint32_t* d = dpay + base;
     const uint32_t wv = (uint32_t)__builtin_amdgcn_readfirstlane(wave_id()), lane = lane_id();
-    constexpr int kCopyAhead = 16;
+    constexpr int kCopyAhead = 8;
     for (uint32_t i0 = wv; i0 < m; i0 += kPackWaves * kCopyAhead) {
       uint32_t val[kCopyAhead], s0[kCopyAhead], nw[kCopyAhead];
 #pragma unroll

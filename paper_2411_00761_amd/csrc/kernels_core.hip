@@ -1056,11 +1056,12 @@ __device__ inline void load_rec(const uint32_t* rec, uint64_t i, int rw, uint32_
   }
 }
 
-template <typename K>
+// RW: record words, a template parameter so that the record stays in registers
+template <typename K, int RW>
 __global__ __launch_bounds__(kThreads) void k_slot_syms_b(const SegDev* S, const uint32_t* pre,
                                                           int R, int F, const uint32_t* perm,
                                                           const K* keys,
-                                                          const uint32_t* rec, int rw,
+                                                          const uint32_t* rec,
                                                           uint64_t ntot, uint32_t* v_rel,
                                                           uint32_t* v_sup, int32_t* q_slot,
                                                           uint32_t tiles) {
@@ -1075,7 +1076,7 @@ __global__ __launch_bounds__(kThreads) void k_slot_syms_b(const SegDev* S, const
   if (valid) {
     const uint32_t i = perm[off + s];
     uint32_t w[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    load_rec(rec, off + i, rw, w);
+    load_rec(rec, off + i, RW, w);
     const int D = g.D;
     const uint64_t pr = (uint64_t)w[0] | (D == 3 ? (uint64_t)w[1] << 32 : 0ull);
     for (int d = 0; d < 3; d++) rel[d][threadIdx.x + 1] = (uint32_t)(pr >> (16 * d)) & 0xFFFFu;
@@ -1092,11 +1093,26 @@ __global__ __launch_bounds__(kThreads) void k_slot_syms_b(const SegDev* S, const
     for (int j = 0; j < kMaxF - 1; j++)
       if (D + j < F) v_sup[(uint64_t)j * ntot + off + s] = sup[j];
     if (q_slot) {
-      const uint64_t key = (uint64_t)keys[off + s];
-      const uint64_t bx = key % g.bn0, rest = key / g.bn0;
-      const uint64_t b3[3] = {bx, rest % g.bn1, rest / g.bn1};
-      for (int d = 0; d < D; d++)
-        q_slot[(uint64_t)d * ntot + off + s] = (int32_t)((b3[d] << g.k) + rel[d][threadIdx.x + 1]);
+      uint64_t b3[3];
+      if constexpr (sizeof(K) == 4) {
+        // 32-bit keys: the block counts per dimension are below 2^32 too, so
+        // the block's coordinates come from 32-bit divisions
+        const uint32_t key = keys[off + s], n0 = (uint32_t)g.bn0, n1 = (uint32_t)g.bn1;
+        const uint32_t rest = key / n0;
+        b3[0] = key - rest * n0;
+        b3[1] = rest % n1;
+        b3[2] = rest / n1;
+      } else {
+        const uint64_t key = (uint64_t)keys[off + s];
+        const uint64_t rest = key / g.bn0;
+        b3[0] = key % g.bn0;
+        b3[1] = rest % g.bn1;
+        b3[2] = rest / g.bn1;
+      }
+#pragma unroll
+      for (int d = 0; d < 3; d++)
+        if (d < D)
+          q_slot[(uint64_t)d * ntot + off + s] = (int32_t)((b3[d] << g.k) + rel[d][threadIdx.x + 1]);
 #pragma unroll
       for (int j = 0; j < kMaxF - 1; j++)
         if (D + j < F) q_slot[(uint64_t)(D + j) * ntot + off + s] = (int32_t)sup[j];
@@ -1107,7 +1123,7 @@ __global__ __launch_bounds__(kThreads) void k_slot_syms_b(const SegDev* S, const
       rel[0][0] = rel[1][0] = rel[2][0] = 0;
     } else {
       const uint64_t j = off + perm[off + s0 - 1];
-      const uint64_t pr = (uint64_t)rec[j * rw] | (g.D == 3 ? (uint64_t)rec[j * rw + 1] << 32 : 0ull);
+      const uint64_t pr = (uint64_t)rec[j * RW] | (g.D == 3 ? (uint64_t)rec[j * RW + 1] << 32 : 0ull);
       for (int d = 0; d < 3; d++) rel[d][0] = (uint32_t)(pr >> (16 * d)) & 0xFFFFu;
     }
   }
@@ -1595,13 +1611,21 @@ void launch_slot_syms_b(const SegDev* S, const uint32_t* pre_256, uint32_t tiles
   const int rw = slot_rec_words(F, D);
   uint64_t bytes = ntot * (4 + 4ull * rw + 4ull * F + (q_slot ? (key32 ? 4 : 8) + 4ull * F : 0));
   const uint32_t g = persistent_grid(tiles, grid);
+  // one instance per key width and record width (2, 4 or 8 words)
+  auto pick = [&](auto kt) {
+    using K = typename decltype(kt)::type;
+    auto* k = k_slot_syms_b<K, 2>;
+    if (rw == 4) k = k_slot_syms_b<K, 4>;
+    else if (rw == 8) k = k_slot_syms_b<K, 8>;
+    return k;
+  };
   if (key32)
-    launch_timed("slot_syms", bytes, k_slot_syms_b<uint32_t>, g, kThreads, 0, s, S, pre_256, R, F,
-                 perm, reinterpret_cast<const uint32_t*>(keys), rec, rw, ntot, v_rel, v_sup,
-                 q_slot, tiles);
+    launch_timed("slot_syms", bytes, pick(std::common_type<uint32_t>()), g, kThreads, 0, s, S,
+                 pre_256, R, F, perm, reinterpret_cast<const uint32_t*>(keys), rec, ntot, v_rel,
+                 v_sup, q_slot, tiles);
   else
-    launch_timed("slot_syms", bytes, k_slot_syms_b<uint64_t>, g, kThreads, 0, s, S, pre_256, R, F,
-                 perm, keys, rec, rw, ntot, v_rel, v_sup, q_slot, tiles);
+    launch_timed("slot_syms", bytes, pick(std::common_type<uint64_t>()), g, kThreads, 0, s, S,
+                 pre_256, R, F, perm, keys, rec, ntot, v_rel, v_sup, q_slot, tiles);
 }
 
 void launch_copy_perm_b(const uint32_t* perm, const SegDev* S, const uint32_t* pre_tile,
