@@ -1525,6 +1525,11 @@ __global__ void k_install(InstallArg a, uint32_t* dst, uint32_t words) {
   for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = a.w[i];
 }
 
+__global__ void k_fetch_host(const uint32_t* src, uint32_t* dst, uint32_t words) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < words) dst[i] = src[i];
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
@@ -1891,6 +1896,13 @@ void launch_install(const void* src, void* dst, size_t bytes, hipStream_t s) {
     dp += chunk;
     bytes -= chunk;
   }
+}
+
+void launch_fetch_host(const void* host_src, void* dst, size_t bytes, hipStream_t s) {
+  const uint32_t words = (uint32_t)(bytes / 4);
+  if (words)
+    k_fetch_host<<<(words + 255) / 256, 256, 0, s>>>(static_cast<const uint32_t*>(host_src),
+                                                      static_cast<uint32_t*>(dst), words);
 }
 
 void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {

@@ -187,6 +187,7 @@ struct lcp_plan_s {
   unsigned long long *ret_dev, *ret_host;
   uint32_t* err;  // the error word (low half of ret_dev[0])
   bool err_clean = false;  // the error word is known to be zero at the stream's tail
+  bool run_clean = false;  // ... and so is a run's return block (cleared behind its read-back)
   int run_len = kTRunStart;  // frames the next temporal run may take
   // temporal frames left to code with the separate code build, after a frame
   // whose residual alphabet outgrew the packing kernel's own build
@@ -513,6 +514,9 @@ struct EncBuild {
   uint64_t cw = 0, values = 0, stage = 0;
   std::vector<uint32_t> hb, cb, fb, kb;
   bool fused = false;  // the packing builds the code (temporal record, a chunk per wave)
+  // the tables go up by one kernel that reads them from pinned host memory
+  // (launch sets the host waits for before it writes the tables again, never captured)
+  bool fetch = false;
 };
 
 // Adds one array of at most nb values to record rec; copy0 < 0 places its
@@ -613,7 +617,20 @@ lcp_status enc_prepare(lcp_plan_s* P, EncBuild& B, EncLaunch* Lo, hipStream_t s)
                     !memcmp(P->enc_cache.data(), P->earr_host, arr_bytes) &&
                     !memcmp(P->enc_cache.data() + arr_bytes, P->epre_host, pre_bytes);
   lcp_status st = LCP_OK;
-  if (B.R > 1 && same) st = upload(P->erec_host, P->erec_dev, sizeof(EncRec) * B.R, s);
+  if (B.fetch && B.R > 1) {
+    // the record table and, unless the device holds them, the array and prefix
+    // tables after it: one span, the same offsets on both sides
+    const uint8_t* h0 = reinterpret_cast<const uint8_t*>(P->erec_host);
+    const uint8_t* hz = same ? h0 + sizeof(EncRec) * B.R
+                             : reinterpret_cast<const uint8_t*>(P->epre_host) + pre_bytes;
+    const size_t span = (size_t)(hz - h0);
+    if (reinterpret_cast<const uint8_t*>(P->earr_host) - h0 !=
+            reinterpret_cast<const uint8_t*>(P->earr_dev) - reinterpret_cast<const uint8_t*>(P->erec_dev) ||
+        reinterpret_cast<const uint8_t*>(P->epre_host) - h0 !=
+            reinterpret_cast<const uint8_t*>(P->epre_dev) - reinterpret_cast<const uint8_t*>(P->erec_dev))
+      return LCP_ERR_DEVICE;  // the layouts keep these tables in the same order and spacing
+    launch_fetch_host(h0, P->erec_dev, (span + 3) & ~(size_t)3, s);
+  } else if (B.R > 1 && same) st = upload(P->erec_host, P->erec_dev, sizeof(EncRec) * B.R, s);
   else if (B.R > 1)
     st = upload_group({{P->erec_host, P->erec_dev, sizeof(EncRec) * B.R},
                        {P->earr_host, P->earr_dev, arr_bytes},
@@ -1290,7 +1307,8 @@ lcp_status run_t(lcp_plan_s* P, const lcp_frame_in* fr, int D, const RunFrame* r
   unsigned long long* offs = P->run_dev + 4 * kTRun;
   uint32_t* run_err = reinterpret_cast<uint32_t*>(offs + kTRun + 1);
   const size_t run_words = 4 * kTRun + kTRun + 2;
-  launch_fill_u32(words, 2 * run_words, 0u, s);
+  if (!P->run_clean) launch_fill_u32(words, 2 * run_words, 0u, s);
+  P->run_clean = false;
   // residual alphabets are short: unless one recently was not, the packing
   // kernel builds each array's code (the residual kernel zeroes the word totals)
   const bool fused = P->fuse_skip == 0 && P->chunk_log2 >= 6 && P->chunk_log2 <= 10;
@@ -1312,6 +1330,7 @@ lcp_status run_t(lcp_plan_s* P, const lcp_frame_in* fr, int D, const RunFrame* r
   EncBuild B;
   B.R = D;
   B.fused = fused;
+  B.fetch = true;  // the host waits for the run below before it writes the tables again
   lcp_status st;
   for (int k = 0; k < D; k++) {
     EncRec& rc = P->erec_host[k];
@@ -1329,6 +1348,9 @@ lcp_status run_t(lcp_plan_s* P, const lcp_frame_in* fr, int D, const RunFrame* r
   }
   if ((st = enc_launch(P, B, out, cap, true, s, run_err, offs, nullptr, words, 8))) return st;
   HIP_OK(hipMemcpyAsync(P->run_host, P->run_dev, 8 * run_words, hipMemcpyDeviceToHost, s));
+  // the next run's return block is cleared while the host waits
+  launch_fill_u32(words, 2 * run_words, 0u, s);
+  P->run_clean = true;
   HIP_OK(hipStreamSynchronize(s));
   if (g_timer_plan == P) timer_collect(P);
   const uint32_t launch_err = (uint32_t)(P->run_host[4 * kTRun + kTRun + 1] & 0xFFFFFFFFull);

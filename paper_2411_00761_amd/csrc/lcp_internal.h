@@ -375,6 +375,10 @@ void launch_t_recon(const int32_t* q_ref, int F, uint64_t n, const GridDev& g,
 // reused as soon as this returns).
 constexpr int kInstallWords = 512;
 void launch_install(const void* src, void* dst, size_t bytes, hipStream_t s);
+// The same for a table in pinned host memory (bytes a multiple of 4) that one
+// kernel reads itself: the source must stay untouched until the stream has
+// passed the launch, and the launch must not be captured into a graph.
+void launch_fetch_host(const void* host_src, void* dst, size_t bytes, hipStream_t s);
 // A chain of up to kChainMax temporal frames reconstructed in one pass:
 // out.p[j][f] holds frame j's int32 residuals and receives its values; frame
 // 0's reference codes are q_ref; q_last (nullable) receives the last frame's.
