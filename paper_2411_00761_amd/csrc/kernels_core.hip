@@ -1525,9 +1525,11 @@ __global__ void k_install(InstallArg a, uint32_t* dst, uint32_t words) {
   for (uint32_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = a.w[i];
 }
 
+// System-scope loads: what the host wrote before the launch is what is read,
+// whatever the GPU's caches hold of the pinned pages from an earlier fetch.
 __global__ void k_fetch_host(const uint32_t* src, uint32_t* dst, uint32_t words) {
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < words) dst[i] = src[i];
+  if (i < words) dst[i] = __hip_atomic_load(src + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
