@@ -188,6 +188,7 @@ struct lcp_plan_s {
   uint32_t* err;  // the error word (low half of ret_dev[0])
   bool err_clean = false;  // the error word is known to be zero at the stream's tail
   bool run_clean = false;  // ... and so is a run's return block (cleared behind its read-back)
+  bool host_pinned = true;  // the bound host tables are pinned (a kernel may read them)
   int run_len = kTRunStart;  // frames the next temporal run may take
   // temporal frames left to code with the separate code build, after a frame
   // whose residual alphabet outgrew the packing kernel's own build
@@ -617,7 +618,7 @@ lcp_status enc_prepare(lcp_plan_s* P, EncBuild& B, EncLaunch* Lo, hipStream_t s)
                     !memcmp(P->enc_cache.data(), P->earr_host, arr_bytes) &&
                     !memcmp(P->enc_cache.data() + arr_bytes, P->epre_host, pre_bytes);
   lcp_status st = LCP_OK;
-  if (B.fetch && B.R > 1) {
+  if (B.fetch && B.R > 1 && P->host_pinned) {
     // the record table and, unless the device holds them, the array and prefix
     // tables after it: one span, the same offsets on both sides
     const uint8_t* h0 = reinterpret_cast<const uint8_t*>(P->erec_host);
@@ -2963,6 +2964,7 @@ extern "C" lcp_status lcp_compress_static(const lcp_params* params, uint64_t n_f
   }
   // binding clears what must start at zero (histogram copies, error word)
   bind_scratch(P, S.dev, S.host, stream);
+  P->host_pinned = false;  // a static host block: tables go up as kernel arguments
   TimerScope ts(P);
   st = compress_independent(P, n_frames, frames, reinterpret_cast<uint8_t*>(out), out_cap,
                             out_offsets, nullptr, perms, stream);
