@@ -126,6 +126,12 @@ def lib():
                                    C.POINTER(C.c_int), P]
         L.lco_bound.argtypes = [C.c_int, C.c_uint64, C.c_int]
         L.lco_bound.restype = C.c_uint64
+        L.lco_dict_bound.argtypes = [C.c_uint64, C.c_int]
+        L.lco_dict_bound.restype = C.c_uint64
+        L.lco_dict_normalise.argtypes = [P, P]
+        L.lco_dict_encode.argtypes = [P, C.c_uint64, C.c_int, P, C.c_uint64,
+                                      C.POINTER(C.c_uint64)]
+        L.lco_dict_decode.argtypes = [P, C.c_uint64, P, C.c_uint64, C.POINTER(C.c_uint64)]
     return _lib
 
 
@@ -438,3 +444,39 @@ def container_retrieve(cont: bytes, frames, eb_mode, eb, n_fields=3, block_log2=
             if j in ps:
                 out[j] = dec
     return out, decoded
+
+
+# ---- dictionary stage: order-0 rANS over bytes (lcp_oracle.h) ----
+DICT_MAGIC = 0x4450434C
+
+
+def dict_normalise(counts) -> np.ndarray:
+    """Byte counts [256] -> frequencies [256] summing to 4096 (0 for absent values)."""
+    c = np.ascontiguousarray(counts, np.uint64)
+    assert c.shape == (256,)
+    f = np.zeros(256, np.uint16)
+    _check(lib().lco_dict_normalise(_ptr(c), _ptr(f)), "lco_dict_normalise")
+    return f
+
+
+def dict_bound(n: int, block_log2: int = 12) -> int:
+    return int(lib().lco_dict_bound(n, block_log2))
+
+
+def dict_encode(data: bytes, block_log2: int = 12) -> bytes:
+    a = np.frombuffer(bytes(data), np.uint8)
+    cap = dict_bound(len(a), block_log2)
+    out = np.zeros(max(cap, 1), np.uint8)
+    size = C.c_uint64(0)
+    _check(lib().lco_dict_encode(_ptr(a) if len(a) else None, len(a), block_log2, _ptr(out), cap,
+                                 C.byref(size)), "lco_dict_encode")
+    return out[:size.value].tobytes()
+
+
+def dict_decode(stream: bytes) -> bytes:
+    a = np.frombuffer(bytes(stream), np.uint8)
+    n = int(np.frombuffer(a[8:16].tobytes(), np.uint64)[0]) if len(a) >= 16 else 0
+    out = np.zeros(max(n, 1), np.uint8)
+    got = C.c_uint64(0)
+    _check(lib().lco_dict_decode(_ptr(a), len(a), _ptr(out), n, C.byref(got)), "lco_dict_decode")
+    return out[:got.value].tobytes()

@@ -1449,3 +1449,168 @@ int lco_search_k(const void* const* x, int F, uint64_t n, const lco_params* p, i
   *k_out = best;
   return LCO_OK;
 }
+
+/* ------------------------------------------------------------------------
+ * Dictionary stage: order-0 rANS over bytes (see lcp_oracle.h for the
+ * stream).  Plain sequential code: one block after the other, one byte at a
+ * time.
+ * ------------------------------------------------------------------------ */
+#define DICT_M (1u << LCO_DICT_SCALE)
+#define DICT_L (1u << 23)
+#define DICT_HDR (4 + 4 + 8 + 2 * 256)
+
+static uint64_t dict_blocks(uint64_t n, int block_log2) {
+  return (n + (1ull << block_log2) - 1) >> block_log2;
+}
+
+uint64_t lco_dict_bound(uint64_t n, int block_log2) {
+  if (block_log2 < 8 || block_log2 > 20) return 0;
+  const uint64_t nb = dict_blocks(n, block_log2);
+  /* a byte costs at most 12 bits (frequency 1 of 4096); a block adds its state */
+  return DICT_HDR + 4 * nb + n + n / 2 + 8 * nb;
+}
+
+int lco_dict_normalise(const uint64_t* counts, uint16_t* freq) {
+  uint64_t n = 0;
+  for (int s = 0; s < 256; s++) n += counts[s];
+  for (int s = 0; s < 256; s++) freq[s] = 0;
+  if (n == 0) return LCO_OK;
+  uint32_t f[256];
+  int64_t sum = 0;
+  for (int s = 0; s < 256; s++) {
+    f[s] = 0;
+    if (counts[s]) {
+      const uint64_t q = (uint64_t)(((unsigned __int128)counts[s] * DICT_M) / n);
+      f[s] = q < 1 ? 1u : (uint32_t)q;
+      sum += f[s];
+    }
+  }
+  if (sum < (int64_t)DICT_M) {
+    int best = -1;
+    for (int s = 0; s < 256; s++)
+      if (counts[s] && (best < 0 || counts[s] > counts[best])) best = s;
+    f[best] += (uint32_t)((int64_t)DICT_M - sum);
+  }
+  int64_t excess = sum - (int64_t)DICT_M;
+  while (excess > 0) {
+    int best = -1;
+    for (int s = 0; s < 256; s++)
+      if (f[s] > 1 && (best < 0 || f[s] > f[best])) best = s;
+    if (best < 0) return LCO_ERR_CORRUPT; /* not reachable: 256 values < 4096 */
+    const uint32_t d = (uint32_t)((int64_t)(f[best] - 1) < excess ? f[best] - 1 : excess);
+    f[best] -= d;
+    excess -= d;
+  }
+  for (int s = 0; s < 256; s++) freq[s] = (uint16_t)f[s];
+  return LCO_OK;
+}
+
+static void put32(uint8_t* p, uint32_t v) {
+  for (int i = 0; i < 4; i++) p[i] = (uint8_t)(v >> (8 * i));
+}
+static uint32_t get32(const uint8_t* p) {
+  return (uint32_t)p[0] | (uint32_t)p[1] << 8 | (uint32_t)p[2] << 16 | (uint32_t)p[3] << 24;
+}
+
+int lco_dict_encode(const uint8_t* in, uint64_t n, int block_log2, uint8_t* out, uint64_t cap,
+                    uint64_t* size) {
+  if ((n && !in) || !out || !size || block_log2 < 8 || block_log2 > 20) return LCO_ERR_ARG;
+  const uint64_t B = 1ull << block_log2, nb = dict_blocks(n, block_log2);
+  const uint64_t need = lco_dict_bound(n, block_log2);
+  *size = need;
+  if (cap < DICT_HDR + 4 * nb) return LCO_ERR_CAPACITY;
+  uint64_t counts[256] = {0};
+  for (uint64_t i = 0; i < n; i++) counts[in[i]]++;
+  uint16_t freq[256];
+  int st = lco_dict_normalise(counts, freq);
+  if (st) return st;
+  uint32_t cum[257];
+  cum[0] = 0;
+  for (int s = 0; s < 256; s++) cum[s + 1] = cum[s] + freq[s];
+  put32(out, LCO_DICT_MAGIC);
+  put32(out + 4, (uint32_t)block_log2);
+  put32(out + 8, (uint32_t)n);
+  put32(out + 12, (uint32_t)(n >> 32));
+  for (int s = 0; s < 256; s++) {
+    out[16 + 2 * s] = (uint8_t)freq[s];
+    out[17 + 2 * s] = (uint8_t)(freq[s] >> 8);
+  }
+  uint8_t* sizes = out + DICT_HDR;
+  uint64_t pos = DICT_HDR + 4 * nb;
+  /* each block codes into a scratch buffer from its end, then is copied */
+  uint8_t* tmp = (uint8_t*)malloc(B + B / 2 + 8);
+  if (!tmp) return LCO_ERR_BUDGET;
+  for (uint64_t b = 0; b < nb; b++) {
+    const uint64_t i0 = b * B, len = n - i0 < B ? n - i0 : B;
+    uint8_t* end = tmp + B + B / 2 + 8;
+    uint8_t* p = end;
+    uint32_t x = DICT_L;
+    for (uint64_t k = len; k-- > 0;) {
+      const uint32_t s = in[i0 + k], f = freq[s];
+      const uint32_t x_max = ((DICT_L >> LCO_DICT_SCALE) << 8) * f;
+      while (x >= x_max) {
+        *--p = (uint8_t)(x & 0xFF);
+        x >>= 8;
+      }
+      x = (x / f) * DICT_M + x % f + cum[s];
+    }
+    p -= 4;
+    put32(p, x);
+    const uint64_t csize = (uint64_t)(end - p);
+    put32(sizes + 4 * b, (uint32_t)csize);
+    if (pos + csize > cap) {
+      free(tmp);
+      *size = pos + csize;
+      return LCO_ERR_CAPACITY;
+    }
+    memcpy(out + pos, p, csize);
+    pos += csize;
+  }
+  free(tmp);
+  *size = pos;
+  return LCO_OK;
+}
+
+int lco_dict_decode(const uint8_t* in, uint64_t size, uint8_t* out, uint64_t cap, uint64_t* n_out) {
+  if (!in || !n_out || size < DICT_HDR) return LCO_ERR_ARG;
+  if (get32(in) != LCO_DICT_MAGIC) return LCO_ERR_CORRUPT;
+  const int block_log2 = (int)get32(in + 4);
+  if (block_log2 < 8 || block_log2 > 20) return LCO_ERR_CORRUPT;
+  const uint64_t n = (uint64_t)get32(in + 8) | (uint64_t)get32(in + 12) << 32;
+  *n_out = n;
+  const uint64_t B = 1ull << block_log2, nb = dict_blocks(n, block_log2);
+  if (nb > (size - DICT_HDR) / 4) return LCO_ERR_CORRUPT;
+  if (n > cap || (n && !out)) return LCO_ERR_CAPACITY;
+  uint16_t freq[256];
+  uint32_t cum[257];
+  cum[0] = 0;
+  for (int s = 0; s < 256; s++) {
+    freq[s] = (uint16_t)(in[16 + 2 * s] | in[17 + 2 * s] << 8);
+    cum[s + 1] = cum[s] + freq[s];
+  }
+  if (n && cum[256] != DICT_M) return LCO_ERR_CORRUPT;
+  uint64_t pos = DICT_HDR + 4 * nb;
+  for (uint64_t b = 0; b < nb; b++) {
+    const uint64_t csize = get32(in + DICT_HDR + 4 * b);
+    const uint64_t i0 = b * B, len = n - i0 < B ? n - i0 : B;
+    if (csize < 4 || pos + csize > size) return LCO_ERR_CORRUPT;
+    const uint8_t* p = in + pos;
+    uint32_t x = get32(p);
+    uint64_t r = 4;
+    for (uint64_t k = 0; k < len; k++) {
+      const uint32_t slot = x & (DICT_M - 1);
+      int s = 0;
+      while (cum[s + 1] <= slot) s++; /* the byte whose interval holds the slot */
+      x = freq[s] * (x >> LCO_DICT_SCALE) + slot - cum[s];
+      while (x < DICT_L) {
+        if (r >= csize) return LCO_ERR_CORRUPT;
+        x = (x << 8) | p[r++];
+      }
+      out[i0 + k] = (uint8_t)s;
+    }
+    if (x != DICT_L || r != csize) return LCO_ERR_CORRUPT;
+    pos += csize;
+  }
+  if (pos != size) return LCO_ERR_CORRUPT;
+  return LCO_OK;
+}

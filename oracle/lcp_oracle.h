@@ -169,6 +169,31 @@ int lco_container_pack(const uint8_t* const* recs, const uint64_t* sizes, uint64
 int lco_container_closure(const uint8_t* cont, uint64_t size, uint64_t k, uint64_t* frames,
                           uint64_t cap, uint64_t* count);
 
+/* ---- dictionary stage (the last coding step, Sec. 6.2.2 and Sec. 7.1) ----
+ * A lossless pass over coded bytes (records): an order-0 range-asymmetric
+ * numeral system (rANS) coder over bytes with one frequency table for the
+ * whole input and independent blocks of 2^block_log2 bytes.  Stream:
+ *   u32 magic 0x4450434C, u32 block_log2, u64 n (input bytes),
+ *   u16 freq[256] (normalised to 4096 when n > 0),
+ *   u32 size[nb] (each block's coded bytes, nb = ceil(n / 2^block_log2)),
+ *   then the blocks' coded bytes back to back.
+ * A block codes its bytes from last to first with a 32-bit state that starts
+ * at 2^23; a byte s with frequency f and cumulative frequency c takes the
+ * state x to (x / f) * 4096 + x % f + c after the low bytes of x are written
+ * out while x >= 2^19 f; the coded block is the final state (4 bytes,
+ * little-endian) followed by the written bytes in the order a decoder reads
+ * them.  Normalisation: f = max(1, floor(count * 4096 / n)) for every byte
+ * value present; a shortfall goes to the most frequent value (ties: the
+ * smaller value); an excess is taken, one value at a time, from the largest
+ * frequencies (ties: the smaller value), none going below 1. */
+#define LCO_DICT_MAGIC 0x4450434Cu
+#define LCO_DICT_SCALE 12
+uint64_t lco_dict_bound(uint64_t n, int block_log2);
+int lco_dict_normalise(const uint64_t* counts /* [256] */, uint16_t* freq /* [256] */);
+int lco_dict_encode(const uint8_t* in, uint64_t n, int block_log2, uint8_t* out, uint64_t cap,
+                    uint64_t* size);
+int lco_dict_decode(const uint8_t* in, uint64_t size, uint8_t* out, uint64_t cap, uint64_t* n);
+
 #ifdef __cplusplus
 }
 #endif
