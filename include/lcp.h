@@ -344,6 +344,44 @@ lcp_status lcp_container_retrieve(lcp_container_t c, lcp_plan_t plan, uint64_t n
                                   uint64_t* decoded, hipStream_t stream);
 void lcp_container_close(lcp_container_t c);
 
+/* ---- Dictionary stage ----
+ * The last coding step of the encoding stage (Sec. 6.2.2) and of LCP-T
+ * (Sec. 7.1), which the paper fills with a general-purpose dictionary coder:
+ * here a lossless pass over any coded bytes (typically the records of a
+ * compress call), an order-0 rANS coder over bytes with one frequency table
+ * for the input and independent blocks of 2^block_log2 bytes (8..20), one
+ * block per GPU lane.  Stream: u32 magic "LCPD", u32 block_log2, u64 n,
+ * u16 freq[256] (normalised to 4096), u32 size[nb] (nb = ceil(n / 2^block_log2)),
+ * then the coded blocks.  A block is coded from its last byte to its first
+ * through a 32-bit state starting at 2^23: a byte of frequency f and
+ * cumulative frequency c writes out the state's low bytes while it is at least
+ * 2^19 f, then takes it to (x / f) 4096 + x % f + c; the coded block is the
+ * final state (4 bytes, little-endian) and the written bytes in reading order.
+ *
+ * lcp_dict_bound: the largest stream for n input bytes (0 for an invalid
+ * block_log2).  lcp_dict_scratch_bytes: the device scratch an encode (encode
+ * != 0) or a decode of n bytes needs.
+ * lcp_dict_encode: in (device, 4-byte aligned, n bytes, read only) to out
+ * (device, out_cap >= lcp_dict_bound(n)); scratch: caller-owned device
+ * memory, 256-byte aligned, of at least lcp_dict_scratch_bytes; *out_size
+ * (host) receives the stream's size.  Synchronises the stream.  Errors:
+ * LCP_ERR_ARG, LCP_ERR_CAPACITY (*out_size = the bound), LCP_ERR_BUDGET
+ * (scratch too small), LCP_ERR_DEVICE.
+ * lcp_dict_decode: a stream of size bytes (device) to out (device, out_cap
+ * bytes); *n_out (host) receives n.  Synchronises the stream (twice).  Errors:
+ * LCP_ERR_ARG, LCP_ERR_CORRUPT (a stream that fails its checks: magic, table
+ * sum, sizes that do not add up to the stream, a block that does not end on
+ * its initial state with all its bytes used), LCP_ERR_CAPACITY (*n_out = n),
+ * LCP_ERR_BUDGET, LCP_ERR_DEVICE. */
+uint64_t lcp_dict_bound(uint64_t n, int block_log2);
+lcp_status lcp_dict_scratch_bytes(uint64_t n, int block_log2, int encode, uint64_t* device_bytes);
+lcp_status lcp_dict_encode(const void* in, uint64_t n, int block_log2, void* out, uint64_t out_cap,
+                           void* scratch, uint64_t scratch_bytes, uint64_t* out_size,
+                           hipStream_t stream);
+lcp_status lcp_dict_decode(const void* in, uint64_t size, void* out, uint64_t out_cap,
+                           void* scratch, uint64_t scratch_bytes, uint64_t* n_out,
+                           hipStream_t stream);
+
 /* ---- Serving: many multi-frame streams, requests overlapped on one device ----
  *
  * A server holds multi-frame streams (each one the state of a multi-frame plan:

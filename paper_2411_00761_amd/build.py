@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblcp_hip.so")
-SOURCES = ["kernels_core.hip", "kernels_codec.hip", "lcp_host.hip", "lcp_server.hip",
+SOURCES = ["kernels_core.hip", "kernels_codec.hip", "lcp_host.hip", "lcp_server.hip", "lcp_dict.hip",
            "lcp_container.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",

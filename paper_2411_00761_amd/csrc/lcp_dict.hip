@@ -1,0 +1,403 @@
+// Dictionary stage: the last coding step of Sec. 6.2.2 and Sec. 7.1 (which
+// the paper fills with a general-purpose dictionary coder), here an order-0
+// range-asymmetric numeral system (rANS) coder over the bytes of coded
+// records.  One frequency table for the whole input (normalised to 4096) and
+// independent blocks of 2^block_log2 bytes, each coded by one lane: a block's
+// bytes go from last to first through a 32-bit state that starts at 2^23; a
+// byte s of frequency f and cumulative frequency c first writes out the low
+// bytes of the state while it is at least 2^19 f, then takes it to
+// (x / f) 4096 + x % f + c.  The coded block is the final state (4 bytes,
+// little-endian) followed by the written bytes in reading order.  Stream: u32
+// magic "LCPD", u32 block_log2, u64 n, u16 freq[256], u32 size[nb], then the
+// coded blocks back to back.
+//
+// Encode: byte histogram; the table (one thread: normalisation, header);
+// blocks coded into staging slots; sizes scanned into offsets (one
+// workgroup); blocks gathered into the stream.  Decode: one header read-back,
+// the sizes scanned and checked, blocks decoded with the table and a
+// 4096-entry slot-to-byte map in LDS.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include "../../include/lcp.h"
+#include "lcp_internal.h"
+
+namespace {
+
+constexpr uint32_t kDMagic = 0x4450434Cu;  // bytes "LCPD"
+constexpr int kDScale = 12;
+constexpr uint32_t kDM = 1u << kDScale;
+constexpr uint32_t kDL = 1u << 23;
+constexpr uint64_t kDHdr = 4 + 4 + 8 + 2 * 256;
+constexpr int kDThreads = 256;
+constexpr int kDLanes = 64;  // blocks per coding workgroup, one per lane
+
+enum : uint32_t { kDErrCorrupt = 1u };
+
+__host__ __device__ inline uint64_t dict_blocks(uint64_t n, int bl) { return (n + (1ull << bl) - 1) >> bl; }
+__host__ __device__ inline uint64_t dict_slot(int bl) { return (((1ull << bl) + (1ull << bl) / 2 + 8) + 15) & ~15ull; }
+
+// Scratch of one call (device, 256-byte aligned pieces).
+struct DictScratch {
+  unsigned long long* counts;  // [256]
+  uint32_t* freq;              // [256]
+  uint32_t* cum;               // [257]
+  uint32_t* sizes;             // [nb]
+  unsigned long long* offs;    // [nb + 1]
+  unsigned long long* total;   // [1] stream bytes
+  uint32_t* err;               // [1]
+  uint8_t* stage;              // [nb][slot] (encode only)
+};
+uint64_t align256(uint64_t b) { return (b + 255) & ~255ull; }
+uint64_t dict_scratch(uint64_t nb, int bl, bool enc, DictScratch* S, uint8_t* base) {
+  uint64_t o = 0;
+  auto take = [&](uint64_t bytes) {
+    uint8_t* p = base ? base + o : nullptr;
+    o += align256(bytes ? bytes : 1);
+    return p;
+  };
+  DictScratch x;
+  x.counts = reinterpret_cast<unsigned long long*>(take(8 * 256));
+  x.freq = reinterpret_cast<uint32_t*>(take(4 * 256));
+  x.cum = reinterpret_cast<uint32_t*>(take(4 * 257));
+  x.sizes = reinterpret_cast<uint32_t*>(take(4 * nb));
+  x.offs = reinterpret_cast<unsigned long long*>(take(8 * (nb + 1)));
+  x.total = reinterpret_cast<unsigned long long*>(take(8));
+  x.err = reinterpret_cast<uint32_t*>(take(4));
+  x.stage = take(enc ? nb * dict_slot(bl) : 0);
+  if (S) *S = x;
+  return o;
+}
+
+__global__ __launch_bounds__(kDThreads) void k_dict_clear(DictScratch S) {
+  const uint32_t t = threadIdx.x;
+  S.counts[t] = 0;
+  if (t == 0) {
+    *S.total = 0;
+    *S.err = 0;
+  }
+}
+
+// Byte histogram: per-workgroup bins in LDS, merged once.
+__global__ __launch_bounds__(kDThreads) void k_dict_hist(const uint8_t* in, uint64_t n,
+                                                         DictScratch S) {
+  __shared__ uint32_t bins[256];
+  bins[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint64_t words = n / 4;
+  const uint32_t* w = reinterpret_cast<const uint32_t*>(in);
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < words; i += stride) {
+    const uint32_t v = w[i];
+#pragma unroll
+    for (int k = 0; k < 4; k++) atomicAdd(&bins[(v >> (8 * k)) & 255u], 1u);
+  }
+  if (blockIdx.x == 0 && threadIdx.x < (n & 3)) atomicAdd(&bins[in[4 * words + threadIdx.x]], 1u);
+  __syncthreads();
+  if (bins[threadIdx.x]) atomicAdd(&S.counts[threadIdx.x], (unsigned long long)bins[threadIdx.x]);
+}
+
+// The table and the stream header, by one thread (256 values).
+__global__ void k_dict_table(uint64_t n, int bl, DictScratch S, uint8_t* out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint32_t f[256];
+  int64_t sum = 0;
+  for (int s = 0; s < 256; s++) {
+    const unsigned long long c = S.counts[s];
+    f[s] = 0;
+    if (c) {
+      // c * 4096 / n without overflow: c < 2^52 for any input below 2^52 bytes
+      const unsigned long long q = (c << kDScale) / n;
+      f[s] = q < 1 ? 1u : (uint32_t)q;
+      sum += f[s];
+    }
+  }
+  if (n && sum < (int64_t)kDM) {
+    int best = -1;
+    for (int s = 0; s < 256; s++)
+      if (S.counts[s] && (best < 0 || S.counts[s] > S.counts[best])) best = s;
+    f[best] += (uint32_t)((int64_t)kDM - sum);
+  }
+  int64_t excess = n ? sum - (int64_t)kDM : 0;
+  while (excess > 0) {
+    int best = -1;
+    for (int s = 0; s < 256; s++)
+      if (f[s] > 1 && (best < 0 || f[s] > f[best])) best = s;
+    if (best < 0) break;  // not reachable: 256 values of at least 1 sum below 4096
+    const int64_t d = (int64_t)(f[best] - 1) < excess ? (int64_t)(f[best] - 1) : excess;
+    f[best] -= (uint32_t)d;
+    excess -= d;
+  }
+  uint32_t c = 0;
+  for (int s = 0; s < 256; s++) {
+    S.freq[s] = f[s];
+    S.cum[s] = c;
+    c += f[s];
+  }
+  S.cum[256] = c;
+  const uint32_t head[4] = {kDMagic, (uint32_t)bl, (uint32_t)n, (uint32_t)(n >> 32)};
+  for (int i = 0; i < 16; i++) out[i] = (uint8_t)(head[i / 4] >> (8 * (i % 4)));
+  for (int s = 0; s < 256; s++) {
+    out[16 + 2 * s] = (uint8_t)f[s];
+    out[17 + 2 * s] = (uint8_t)(f[s] >> 8);
+  }
+}
+
+// One block per lane, coded from its last byte to its first into the end of
+// its staging slot (at most 1.5 bytes per byte plus the state fit the slot).
+__global__ __launch_bounds__(kDLanes) void k_dict_encode(const uint8_t* in, uint64_t n, int bl,
+                                                         uint64_t nb, DictScratch S) {
+  __shared__ uint32_t freq[256], cum[256];
+  for (int s = threadIdx.x; s < 256; s += kDLanes) {
+    freq[s] = S.freq[s];
+    cum[s] = S.cum[s];
+  }
+  __syncthreads();
+  const uint64_t b = (uint64_t)blockIdx.x * kDLanes + threadIdx.x;
+  if (b >= nb) return;
+  const uint64_t B = 1ull << bl, slot = dict_slot(bl);
+  const uint64_t i0 = b * B, len = n - i0 < B ? n - i0 : B;
+  uint8_t* const lo = S.stage + b * slot;
+  uint8_t* const end = lo + slot;
+  uint8_t* p = end;
+  uint32_t x = kDL;
+  for (uint64_t k = len; k-- > 0;) {
+    const uint32_t s = in[i0 + k], f = freq[s];
+    const uint32_t x_max = ((kDL >> kDScale) << 8) * f;
+    while (x >= x_max) {
+      if (p - lo <= 4) {  // never taken: a block codes into at most 1.5 bytes per byte + 5
+        S.sizes[b] = 0;
+        atomicOr(S.err, kDErrCorrupt);
+        return;
+      }
+      *--p = (uint8_t)(x & 0xFFu);
+      x >>= 8;
+    }
+    x = (x / f) * kDM + x % f + cum[s];
+  }
+  p -= 4;
+  p[0] = (uint8_t)x;
+  p[1] = (uint8_t)(x >> 8);
+  p[2] = (uint8_t)(x >> 16);
+  p[3] = (uint8_t)(x >> 24);
+  S.sizes[b] = (uint32_t)(end - p);
+}
+
+// Exclusive scan of the block sizes (one workgroup: a contiguous run of blocks
+// per thread), the stream's total size, and, when encoding, the size table
+// written into the stream.  When decoding the sizes come from the stream and
+// must add up to its size.
+__global__ __launch_bounds__(kDThreads) void k_dict_offsets(const uint32_t* sizes, uint64_t nb,
+                                                            DictScratch S, uint8_t* out,
+                                                            uint64_t check_total) {
+  __shared__ unsigned long long part[kDThreads];
+  const uint64_t per = (nb + kDThreads - 1) / kDThreads;
+  const uint64_t j0 = threadIdx.x * per, j1 = j0 + per < nb ? j0 + per : nb;
+  unsigned long long sum = 0;
+  for (uint64_t j = j0; j < j1; j++) sum += sizes[j];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long run = 0;
+    for (int t = 0; t < kDThreads; t++) {
+      const unsigned long long v = part[t];
+      part[t] = run;
+      run += v;
+    }
+    S.offs[nb] = run;
+    const unsigned long long total = kDHdr + 4 * nb + run;
+    *S.total = total;
+    if (check_total && total != check_total) atomicOr(S.err, kDErrCorrupt);
+  }
+  __syncthreads();
+  unsigned long long o = part[threadIdx.x];
+  for (uint64_t j = j0; j < j1; j++) {
+    S.offs[j] = o;
+    const uint32_t v = sizes[j];
+    if (out) {
+      uint8_t* d = out + kDHdr + 4 * j;
+      d[0] = (uint8_t)v;
+      d[1] = (uint8_t)(v >> 8);
+      d[2] = (uint8_t)(v >> 16);
+      d[3] = (uint8_t)(v >> 24);
+    }
+    o += v;
+  }
+}
+
+// Coded blocks from their staging slots into the stream, one workgroup each.
+__global__ __launch_bounds__(kDThreads) void k_dict_gather(uint64_t nb, int bl, DictScratch S,
+                                                           uint8_t* out) {
+  const uint64_t b = blockIdx.x;
+  if (b >= nb) return;
+  const uint64_t slot = dict_slot(bl), size = S.sizes[b];
+  const uint8_t* src = S.stage + b * slot + slot - size;
+  uint8_t* dst = out + kDHdr + 4 * nb + S.offs[b];
+  for (uint64_t i = threadIdx.x; i < size; i += kDThreads) dst[i] = src[i];
+}
+
+// One block per lane: the state read from the block's first four bytes, then
+// per byte the slot x mod 4096 names the byte, the state steps back and takes
+// in bytes while it is below 2^23.  A block must end on the initial state and
+// use exactly its bytes.
+__global__ __launch_bounds__(kDLanes) void k_dict_decode(const uint8_t* in, uint64_t n, int bl,
+                                                         uint64_t nb, DictScratch S,
+                                                         uint8_t* out) {
+  __shared__ uint32_t freq[256], cum[257];
+  __shared__ uint8_t sym[kDM];
+  __shared__ uint32_t bad;
+  if (threadIdx.x == 0) bad = 0;
+  for (int s = threadIdx.x; s < 256; s += kDLanes)
+    freq[s] = (uint32_t)in[16 + 2 * s] | (uint32_t)in[17 + 2 * s] << 8;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t c = 0;
+    for (int s = 0; s < 256; s++) {
+      cum[s] = c;
+      c += freq[s];
+    }
+    cum[256] = c;
+    if (c != kDM) bad = 1;
+  }
+  __syncthreads();
+  if (bad) {
+    if (threadIdx.x == 0) atomicOr(S.err, kDErrCorrupt);
+    return;
+  }
+  // the slot map: slot i belongs to the byte whose interval [cum, cum + freq) holds it
+  for (uint32_t i = threadIdx.x; i < kDM; i += kDLanes) {
+    uint32_t lo = 0, hi = 256;  // cum[lo] <= i < cum[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (cum[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    sym[i] = (uint8_t)lo;
+  }
+  __syncthreads();
+  const uint64_t b = (uint64_t)blockIdx.x * kDLanes + threadIdx.x;
+  if (b >= nb) return;
+  const uint64_t B = 1ull << bl;
+  const uint64_t i0 = b * B, len = n - i0 < B ? n - i0 : B;
+  const uint64_t csize = S.sizes[b];
+  const uint8_t* p = in + kDHdr + 4 * nb + S.offs[b];
+  if (csize < 4) {
+    atomicOr(S.err, kDErrCorrupt);
+    return;
+  }
+  uint32_t x = (uint32_t)p[0] | (uint32_t)p[1] << 8 | (uint32_t)p[2] << 16 | (uint32_t)p[3] << 24;
+  uint64_t r = 4;
+  for (uint64_t k = 0; k < len; k++) {
+    const uint32_t slot = x & (kDM - 1);
+    const uint32_t s = sym[slot];
+    x = freq[s] * (x >> kDScale) + slot - cum[s];
+    while (x < kDL) {
+      if (r >= csize) {
+        atomicOr(S.err, kDErrCorrupt);
+        return;
+      }
+      x = (x << 8) | p[r++];
+    }
+    out[i0 + k] = (uint8_t)s;
+  }
+  if (x != kDL || r != csize) atomicOr(S.err, kDErrCorrupt);
+}
+
+lcp_status dict_args(int bl) { return bl < 8 || bl > 20 ? LCP_ERR_ARG : LCP_OK; }
+
+}  // namespace
+
+extern "C" {
+
+uint64_t lcp_dict_bound(uint64_t n, int block_log2) {
+  if (dict_args(block_log2)) return 0;
+  const uint64_t nb = dict_blocks(n, block_log2);
+  return kDHdr + 4 * nb + n + n / 2 + 8 * nb;
+}
+
+lcp_status lcp_dict_scratch_bytes(uint64_t n, int block_log2, int encode, uint64_t* device_bytes) {
+  if (!device_bytes || dict_args(block_log2)) return LCP_ERR_ARG;
+  *device_bytes = dict_scratch(dict_blocks(n, block_log2), block_log2, encode != 0, nullptr, nullptr);
+  return LCP_OK;
+}
+
+lcp_status lcp_dict_encode(const void* in, uint64_t n, int block_log2, void* out, uint64_t out_cap,
+                           void* scratch, uint64_t scratch_bytes, uint64_t* out_size,
+                           hipStream_t stream) {
+  if (!out_size || !out || !scratch || (n && !in) || dict_args(block_log2)) return LCP_ERR_ARG;
+  if (((uintptr_t)in & 3) || ((uintptr_t)scratch & 255)) return LCP_ERR_ARG;
+  const uint64_t nb = dict_blocks(n, block_log2);
+  if (nb > 0x7FFFFFFFull) return LCP_ERR_ARG;
+  DictScratch S;
+  if (dict_scratch(nb, block_log2, true, &S, static_cast<uint8_t*>(scratch)) > scratch_bytes)
+    return LCP_ERR_BUDGET;
+  const uint64_t bound = lcp_dict_bound(n, block_log2);
+  *out_size = bound;
+  // the worst case must fit: blocks are placed before their sizes are known
+  if (out_cap < bound) return LCP_ERR_CAPACITY;
+  uint8_t* o = static_cast<uint8_t*>(out);
+  const uint8_t* src = static_cast<const uint8_t*>(in);
+  k_dict_clear<<<1, kDThreads, 0, stream>>>(S);
+  if (n) {
+    const uint64_t hb = (n / 4 + kDThreads * 16 - 1) / (kDThreads * 16);
+    k_dict_hist<<<(uint32_t)(hb < 1 ? 1 : (hb > 4096 ? 4096 : hb)), kDThreads, 0, stream>>>(src, n,
+                                                                                            S);
+  }
+  k_dict_table<<<1, 64, 0, stream>>>(n, block_log2, S, o);
+  if (nb) {
+    k_dict_encode<<<(uint32_t)((nb + kDLanes - 1) / kDLanes), kDLanes, 0, stream>>>(
+        src, n, block_log2, nb, S);
+  }
+  k_dict_offsets<<<1, kDThreads, 0, stream>>>(S.sizes, nb, S, o, 0);
+  if (nb) k_dict_gather<<<(uint32_t)nb, kDThreads, 0, stream>>>(nb, block_log2, S, o);
+  unsigned long long total = 0;
+  uint32_t err = 0;
+  if (hipMemcpyAsync(&total, S.total, 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipMemcpyAsync(&err, S.err, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return LCP_ERR_DEVICE;
+  *out_size = total;
+  return err ? LCP_ERR_DEVICE : LCP_OK;
+}
+
+lcp_status lcp_dict_decode(const void* in, uint64_t size, void* out, uint64_t out_cap,
+                           void* scratch, uint64_t scratch_bytes, uint64_t* n_out,
+                           hipStream_t stream) {
+  if (!in || !n_out || !scratch || size < kDHdr || ((uintptr_t)scratch & 255))
+    return LCP_ERR_ARG;
+  if (size > (1ull << 40)) return LCP_ERR_ARG;
+  uint32_t head[4];
+  if (hipMemcpyAsync(head, in, 16, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return LCP_ERR_DEVICE;
+  if (head[0] != kDMagic || dict_args((int)head[1])) return LCP_ERR_CORRUPT;
+  const int bl = (int)head[1];
+  const uint64_t n = (uint64_t)head[2] | (uint64_t)head[3] << 32;
+  *n_out = n;
+  const uint64_t nb = dict_blocks(n, bl);
+  if (nb > (size - kDHdr) / 4) return LCP_ERR_CORRUPT;
+  if (n > out_cap || (n && !out)) return LCP_ERR_CAPACITY;
+  DictScratch S;
+  if (dict_scratch(nb, bl, false, &S, static_cast<uint8_t*>(scratch)) > scratch_bytes)
+    return LCP_ERR_BUDGET;
+  const uint8_t* src = static_cast<const uint8_t*>(in);
+  k_dict_clear<<<1, kDThreads, 0, stream>>>(S);
+  // the stream's sizes (at byte offset kDHdr), copied into scratch
+  if (nb && hipMemcpyAsync(S.sizes, src + kDHdr, 4 * nb, hipMemcpyDeviceToDevice, stream) != hipSuccess)
+    return LCP_ERR_DEVICE;
+  k_dict_offsets<<<1, kDThreads, 0, stream>>>(S.sizes, nb, S, nullptr, size);
+  uint32_t err = 0;
+  if (hipMemcpyAsync(&err, S.err, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return LCP_ERR_DEVICE;
+  if (err) return LCP_ERR_CORRUPT;  // the blocks would reach past the stream
+  if (nb)
+    k_dict_decode<<<(uint32_t)((nb + kDLanes - 1) / kDLanes), kDLanes, 0, stream>>>(
+        src, n, bl, nb, S, static_cast<uint8_t*>(out));
+  if (hipMemcpyAsync(&err, S.err, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+      hipStreamSynchronize(stream) != hipSuccess)
+    return LCP_ERR_DEVICE;
+  return err ? LCP_ERR_CORRUPT : LCP_OK;
+}
+
+}  // extern "C"

@@ -31,7 +31,8 @@ EXPORTED = ["lcp_plan", "lcp_plan_destroy", "lcp_plan_reset", "lcp_plan_block_lo
             "lcp_plan_get_tuning", "lcp_plan_autotune", "lcp_server_counts",
             "lcp_server_hold", "lcp_container_pack", "lcp_container_open",
             "lcp_container_info", "lcp_container_closure", "lcp_container_retrieve",
-            "lcp_container_close"]
+            "lcp_container_close", "lcp_dict_bound", "lcp_dict_scratch_bytes",
+            "lcp_dict_encode", "lcp_dict_decode"]
 REQ_COMPRESS, REQ_DECOMPRESS = 1, 2
 
 
@@ -558,3 +559,65 @@ class Container:
         _check(lib().lcp_container_retrieve(self.h, plan.h, n, fr, fo, C.byref(dec),
                                             _stream_handle()), "lcp_container_retrieve")
         return dec.value
+
+
+# ---- dictionary stage (lcp_dict_*): marshalling only ----
+def _dict_lib():
+    L = lib()
+    if not getattr(L, "_dict_types", False):
+        P = C.c_void_p
+        L.lcp_dict_bound.argtypes = [C.c_uint64, C.c_int]
+        L.lcp_dict_bound.restype = C.c_uint64
+        L.lcp_dict_scratch_bytes.argtypes = [C.c_uint64, C.c_int, C.c_int, C.POINTER(C.c_uint64)]
+        L.lcp_dict_encode.argtypes = [P, C.c_uint64, C.c_int, P, C.c_uint64, P, C.c_uint64,
+                                      C.POINTER(C.c_uint64), P]
+        L.lcp_dict_decode.argtypes = [P, C.c_uint64, P, C.c_uint64, P, C.c_uint64,
+                                      C.POINTER(C.c_uint64), P]
+        L._dict_types = True
+    return L
+
+
+def dict_bound(n: int, block_log2: int = 12) -> int:
+    return int(_dict_lib().lcp_dict_bound(n, block_log2))
+
+
+def dict_scratch_bytes(n: int, block_log2: int = 12, encode: bool = True) -> int:
+    b = C.c_uint64(0)
+    _check(_dict_lib().lcp_dict_scratch_bytes(n, block_log2, 1 if encode else 0, C.byref(b)),
+           "lcp_dict_scratch_bytes")
+    return b.value
+
+
+def dict_encode(buf, n: int = None, block_log2: int = 12, out=None, scratch=None):
+    """lcp_dict_encode on the first n bytes of a device uint8 tensor; returns
+    (stream uint8 tensor, stream size)."""
+    import torch
+    n = buf.numel() if n is None else int(n)
+    if out is None:
+        out = torch.empty(dict_bound(n, block_log2), dtype=torch.uint8, device=buf.device)
+    if scratch is None:
+        scratch = torch.empty(dict_scratch_bytes(n, block_log2, True), dtype=torch.uint8,
+                              device=buf.device)
+    size = C.c_uint64(0)
+    _check(_dict_lib().lcp_dict_encode(buf.data_ptr(), n, block_log2, out.data_ptr(), out.numel(),
+                                       scratch.data_ptr(), scratch.numel(), C.byref(size),
+                                       torch.cuda.current_stream(buf.device).cuda_stream),
+           "lcp_dict_encode")
+    return out, size.value
+
+
+def dict_decode(stream, size: int, n: int, block_log2: int = 12, out=None, scratch=None):
+    """lcp_dict_decode of a stream of size bytes holding n bytes (block_log2 as
+    encoded); returns the decoded uint8 tensor."""
+    import torch
+    if out is None:
+        out = torch.empty(max(n, 1), dtype=torch.uint8, device=stream.device)
+    if scratch is None:
+        scratch = torch.empty(dict_scratch_bytes(n, block_log2, False), dtype=torch.uint8,
+                              device=stream.device)
+    got = C.c_uint64(0)
+    _check(_dict_lib().lcp_dict_decode(stream.data_ptr(), size, out.data_ptr(), out.numel(),
+                                       scratch.data_ptr(), scratch.numel(), C.byref(got),
+                                       torch.cuda.current_stream(stream.device).cuda_stream),
+           "lcp_dict_decode")
+    return out[:got.value]
