@@ -621,7 +621,47 @@ def bench_next_rows(args, torch, lcp, frames, k, steps=2, n_random=16):
         "records_decoded_per_request_max": int(np.max(decoded)),
         "checked": "every single-frame request equals the sequential retrieval bit for bit"}
     cont.close()
-    del plan, dplan, out, cbuf, seq, one
+    del cbuf, seq, one
+
+    # the dictionary stage (lcp_dict_*) over the float stream's records, then over
+    # the records of frames that do not move (frame 0 eight times: every temporal
+    # residual is zero, one Huffman bit per value); each stream decoded and checked
+    def dict_leg(recs, what, reps=3, bl=11):
+        nbytes = recs.numel()
+        scr_e = torch.empty(lcp.dict_scratch_bytes(nbytes, bl, True), dtype=torch.uint8, device=dev)
+        scr_d = torch.empty(lcp.dict_scratch_bytes(nbytes, bl, False), dtype=torch.uint8, device=dev)
+        sout = torch.empty(lcp.dict_bound(nbytes, bl), dtype=torch.uint8, device=dev)
+        back = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        te, td = [], []
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            _, ssize = lcp.dict_encode(recs, block_log2=bl, out=sout, scratch=scr_e)
+            t1 = time.perf_counter()
+            lcp.dict_decode(sout, ssize, nbytes, block_log2=bl, out=back, scratch=scr_d)
+            torch.cuda.synchronize()
+            te.append(t1 - t0)
+            td.append(time.perf_counter() - t1)
+        assert torch.equal(back, recs), what
+        te, td = sorted(te[1:])[reps // 2], sorted(td[1:])[reps // 2]
+        return {"workload": what, "block_log2": bl, "input_bytes": nbytes, "stream_bytes": ssize,
+                "size_ratio": ssize / nbytes, "encode_GBps": nbytes / te / 1e9,
+                "decode_GBps": nbytes / td / 1e9, "checked": "decoded stream equals the records"}
+
+    recs = out[:offs[-1]]
+    res["dictionary"] = dict_leg(recs, f"the float trajectory's {nf} records "
+                                       f"({offs[-1]} bytes, CR {size_d / offs[-1]:.2f})")
+    res["dictionary"]["ratio_with_stage"] = size_d / res["dictionary"]["stream_bytes"]
+    still = [frames[0]] * 8
+    plan.reset()
+    out8, offs8, used8, _ = plan.compress(still)
+    size_8 = sum(f.numel() * 4 for f in still)
+    res["dictionary_static"] = dict_leg(out8[:offs8[-1]], "frame 0 eight times (particles that "
+                                        f"do not move; CR {size_8 / offs8[-1]:.2f} before the stage: "
+                                        "the temporal records are a few bytes each, the spatial "
+                                        "record is the rest)")
+    res["dictionary_static"]["ratio_with_stage"] = size_8 / res["dictionary_static"]["stream_bytes"]
+    del plan, dplan, out, out8
     torch.cuda.empty_cache()
     return res
 
