@@ -362,7 +362,7 @@ void lcp_container_close(lcp_container_t c);
  * block_log2).  lcp_dict_scratch_bytes: the device scratch an encode (encode
  * != 0) or a decode of n bytes needs.
  * lcp_dict_encode: in (device, 4-byte aligned, n bytes, read only) to out
- * (device, out_cap >= lcp_dict_bound(n)); scratch: caller-owned device
+ * (device, 4-byte aligned, out_cap >= lcp_dict_bound(n)); scratch: caller-owned device
  * memory, 256-byte aligned, of at least lcp_dict_scratch_bytes; *out_size
  * (host) receives the stream's size.  Synchronises the stream.  Errors:
  * LCP_ERR_ARG, LCP_ERR_CAPACITY (*out_size = the bound), LCP_ERR_BUDGET

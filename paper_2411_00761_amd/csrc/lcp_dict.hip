@@ -12,10 +12,12 @@
 // coded blocks back to back.
 //
 // Encode: byte histogram; the table (one thread: normalisation, header);
-// blocks coded into staging slots; sizes scanned into offsets (one
-// workgroup); blocks gathered into the stream.  Decode: one header read-back,
-// the sizes scanned and checked, blocks decoded with the table and a
-// 4096-entry slot-to-byte map in LDS.
+// blocks coded into staging slots (each lane also writes its block's size
+// into the stream's size table); the sizes scanned into offsets (the
+// library's device scan); blocks gathered into the stream, a wave per block.
+// Decode: one header read-back, the sizes scanned and checked against the
+// stream's size, blocks decoded with the table and a 4096-entry slot-to-byte
+// map in LDS.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -43,9 +45,11 @@ struct DictScratch {
   uint32_t* freq;              // [256]
   uint32_t* cum;               // [257]
   uint32_t* sizes;             // [nb]
-  unsigned long long* offs;    // [nb + 1]
+  uint64_t* offs;              // [nb + 1]
   unsigned long long* total;   // [1] stream bytes
   uint32_t* err;               // [1]
+  uint64_t* tmp;               // scan scratch
+  uint32_t* sym;               // [4096 / 4] decode: the slot-to-byte map, four slots a word
   uint8_t* stage;              // [nb][slot] (encode only)
 };
 uint64_t align256(uint64_t b) { return (b + 255) & ~255ull; }
@@ -61,9 +65,11 @@ uint64_t dict_scratch(uint64_t nb, int bl, bool enc, DictScratch* S, uint8_t* ba
   x.freq = reinterpret_cast<uint32_t*>(take(4 * 256));
   x.cum = reinterpret_cast<uint32_t*>(take(4 * 257));
   x.sizes = reinterpret_cast<uint32_t*>(take(4 * nb));
-  x.offs = reinterpret_cast<unsigned long long*>(take(8 * (nb + 1)));
+  x.offs = reinterpret_cast<uint64_t*>(take(8 * (nb + 1)));
   x.total = reinterpret_cast<unsigned long long*>(take(8));
   x.err = reinterpret_cast<uint32_t*>(take(4));
+  x.tmp = reinterpret_cast<uint64_t*>(take(8 * lcp::scan_tmp_elems(nb + 1)));
+  x.sym = reinterpret_cast<uint32_t*>(take(kDM));
   x.stage = take(enc ? nb * dict_slot(bl) : 0);
   if (S) *S = x;
   return o;
@@ -146,7 +152,8 @@ __global__ void k_dict_table(uint64_t n, int bl, DictScratch S, uint8_t* out) {
 // One block per lane, coded from its last byte to its first into the end of
 // its staging slot (at most 1.5 bytes per byte plus the state fit the slot).
 __global__ __launch_bounds__(kDLanes) void k_dict_encode(const uint8_t* in, uint64_t n, int bl,
-                                                         uint64_t nb, DictScratch S) {
+                                                         uint64_t nb, DictScratch S,
+                                                         uint8_t* out) {
   __shared__ uint32_t freq[256], cum[256];
   for (int s = threadIdx.x; s < 256; s += kDLanes) {
     freq[s] = S.freq[s];
@@ -167,6 +174,8 @@ __global__ __launch_bounds__(kDLanes) void k_dict_encode(const uint8_t* in, uint
     while (x >= x_max) {
       if (p - lo <= 4) {  // never taken: a block codes into at most 1.5 bytes per byte + 5
         S.sizes[b] = 0;
+        S.offs[b] = 0;
+        reinterpret_cast<uint32_t*>(out + kDHdr)[b] = 0;
         atomicOr(S.err, kDErrCorrupt);
         return;
       }
@@ -180,60 +189,70 @@ __global__ __launch_bounds__(kDLanes) void k_dict_encode(const uint8_t* in, uint
   p[1] = (uint8_t)(x >> 8);
   p[2] = (uint8_t)(x >> 16);
   p[3] = (uint8_t)(x >> 24);
-  S.sizes[b] = (uint32_t)(end - p);
+  const uint32_t size = (uint32_t)(end - p);
+  S.sizes[b] = size;
+  S.offs[b] = size;
+  reinterpret_cast<uint32_t*>(out + kDHdr)[b] = size;  // the stream's size table (4-byte aligned)
 }
 
-// Exclusive scan of the block sizes (one workgroup: a contiguous run of blocks
-// per thread), the stream's total size, and, when encoding, the size table
-// written into the stream.  When decoding the sizes come from the stream and
-// must add up to its size.
-__global__ __launch_bounds__(kDThreads) void k_dict_offsets(const uint32_t* sizes, uint64_t nb,
-                                                            DictScratch S, uint8_t* out,
-                                                            uint64_t check_total) {
-  __shared__ unsigned long long part[kDThreads];
-  const uint64_t per = (nb + kDThreads - 1) / kDThreads;
-  const uint64_t j0 = threadIdx.x * per, j1 = j0 + per < nb ? j0 + per : nb;
-  unsigned long long sum = 0;
-  for (uint64_t j = j0; j < j1; j++) sum += sizes[j];
-  part[threadIdx.x] = sum;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned long long run = 0;
-    for (int t = 0; t < kDThreads; t++) {
-      const unsigned long long v = part[t];
-      part[t] = run;
-      run += v;
-    }
-    S.offs[nb] = run;
-    const unsigned long long total = kDHdr + 4 * nb + run;
-    *S.total = total;
-    if (check_total && total != check_total) atomicOr(S.err, kDErrCorrupt);
-  }
-  __syncthreads();
-  unsigned long long o = part[threadIdx.x];
-  for (uint64_t j = j0; j < j1; j++) {
-    S.offs[j] = o;
-    const uint32_t v = sizes[j];
-    if (out) {
-      uint8_t* d = out + kDHdr + 4 * j;
-      d[0] = (uint8_t)v;
-      d[1] = (uint8_t)(v >> 8);
-      d[2] = (uint8_t)(v >> 16);
-      d[3] = (uint8_t)(v >> 24);
-    }
-    o += v;
-  }
+// The block sizes as u64 (decoding: from the stream), to be scanned in place.
+__global__ __launch_bounds__(kDThreads) void k_dict_widen(uint64_t nb, DictScratch S) {
+  const uint64_t j = (uint64_t)blockIdx.x * kDThreads + threadIdx.x;
+  if (j < nb) S.offs[j] = S.sizes[j];
+}
+
+// After the exclusive scan: offs[nb] and the stream's total size; when
+// decoding the sizes must add up to the stream.
+__global__ void k_dict_total(uint64_t nb, DictScratch S, uint64_t check_total) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const unsigned long long run = nb ? S.offs[nb - 1] + S.sizes[nb - 1] : 0ull;
+  S.offs[nb] = run;
+  const unsigned long long total = kDHdr + 4 * nb + run;
+  *S.total = total;
+  if (check_total && total != check_total) atomicOr(S.err, kDErrCorrupt);
 }
 
 // Coded blocks from their staging slots into the stream, one workgroup each.
 __global__ __launch_bounds__(kDThreads) void k_dict_gather(uint64_t nb, int bl, DictScratch S,
                                                            uint8_t* out) {
-  const uint64_t b = blockIdx.x;
+  const uint64_t b = (uint64_t)blockIdx.x * (kDThreads / 64) + threadIdx.x / 64;
   if (b >= nb) return;
   const uint64_t slot = dict_slot(bl), size = S.sizes[b];
   const uint8_t* src = S.stage + b * slot + slot - size;
   uint8_t* dst = out + kDHdr + 4 * nb + S.offs[b];
-  for (uint64_t i = threadIdx.x; i < size; i += kDThreads) dst[i] = src[i];
+  for (uint64_t i = threadIdx.x % 64; i < size; i += 64) dst[i] = src[i];
+}
+
+// The slot-to-byte map of a stream's table (slot i belongs to the byte whose
+// interval [cum, cum + freq) holds it), built once for the decode workgroups;
+// a table that does not sum to 4096 flags the stream.
+__global__ __launch_bounds__(kDThreads) void k_dict_slots(const uint8_t* in, DictScratch S) {
+  __shared__ uint32_t cum[257];
+  if (threadIdx.x == 0) {
+    uint32_t c = 0;
+    for (int s = 0; s < 256; s++) {
+      cum[s] = c;
+      c += (uint32_t)in[16 + 2 * s] | (uint32_t)in[17 + 2 * s] << 8;
+    }
+    cum[256] = c;
+    if (c != kDM && blockIdx.x == 0) atomicOr(S.err, kDErrCorrupt);
+  }
+  __syncthreads();
+  if (cum[256] != kDM) return;
+  // four consecutive slots per thread, packed into one word
+  const uint32_t w = blockIdx.x * kDThreads + threadIdx.x;  // < kDM / 4
+  uint32_t packed = 0;
+  for (uint32_t k = 0; k < 4; k++) {
+    const uint32_t i = 4 * w + k;
+    uint32_t lo = 0, hi = 256;  // cum[lo] <= i < cum[hi]
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (cum[mid] <= i) lo = mid;
+      else hi = mid;
+    }
+    packed |= lo << (8 * k);
+  }
+  S.sym[w] = packed;
 }
 
 // One block per lane: the state read from the block's first four bytes, then
@@ -244,11 +263,11 @@ __global__ __launch_bounds__(kDLanes) void k_dict_decode(const uint8_t* in, uint
                                                          uint64_t nb, DictScratch S,
                                                          uint8_t* out) {
   __shared__ uint32_t freq[256], cum[257];
-  __shared__ uint8_t sym[kDM];
-  __shared__ uint32_t bad;
-  if (threadIdx.x == 0) bad = 0;
+  __shared__ uint32_t sym4[kDM / 4];
+  const uint8_t* sym = reinterpret_cast<const uint8_t*>(sym4);
   for (int s = threadIdx.x; s < 256; s += kDLanes)
     freq[s] = (uint32_t)in[16 + 2 * s] | (uint32_t)in[17 + 2 * s] << 8;
+  for (uint32_t i = threadIdx.x; i < kDM / 4; i += kDLanes) sym4[i] = S.sym[i];
   __syncthreads();
   if (threadIdx.x == 0) {
     uint32_t c = 0;
@@ -257,22 +276,6 @@ __global__ __launch_bounds__(kDLanes) void k_dict_decode(const uint8_t* in, uint
       c += freq[s];
     }
     cum[256] = c;
-    if (c != kDM) bad = 1;
-  }
-  __syncthreads();
-  if (bad) {
-    if (threadIdx.x == 0) atomicOr(S.err, kDErrCorrupt);
-    return;
-  }
-  // the slot map: slot i belongs to the byte whose interval [cum, cum + freq) holds it
-  for (uint32_t i = threadIdx.x; i < kDM; i += kDLanes) {
-    uint32_t lo = 0, hi = 256;  // cum[lo] <= i < cum[hi]
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) / 2;
-      if (cum[mid] <= i) lo = mid;
-      else hi = mid;
-    }
-    sym[i] = (uint8_t)lo;
   }
   __syncthreads();
   const uint64_t b = (uint64_t)blockIdx.x * kDLanes + threadIdx.x;
@@ -325,7 +328,7 @@ lcp_status lcp_dict_encode(const void* in, uint64_t n, int block_log2, void* out
                            void* scratch, uint64_t scratch_bytes, uint64_t* out_size,
                            hipStream_t stream) {
   if (!out_size || !out || !scratch || (n && !in) || dict_args(block_log2)) return LCP_ERR_ARG;
-  if (((uintptr_t)in & 3) || ((uintptr_t)scratch & 255)) return LCP_ERR_ARG;
+  if (((uintptr_t)in & 3) || ((uintptr_t)out & 3) || ((uintptr_t)scratch & 255)) return LCP_ERR_ARG;
   const uint64_t nb = dict_blocks(n, block_log2);
   if (nb > 0x7FFFFFFFull) return LCP_ERR_ARG;
   DictScratch S;
@@ -346,10 +349,13 @@ lcp_status lcp_dict_encode(const void* in, uint64_t n, int block_log2, void* out
   k_dict_table<<<1, 64, 0, stream>>>(n, block_log2, S, o);
   if (nb) {
     k_dict_encode<<<(uint32_t)((nb + kDLanes - 1) / kDLanes), kDLanes, 0, stream>>>(
-        src, n, block_log2, nb, S);
+        src, n, block_log2, nb, S, o);
+    lcp::scan_device<uint64_t>(S.offs, nb, nullptr, true, S.tmp, stream);
   }
-  k_dict_offsets<<<1, kDThreads, 0, stream>>>(S.sizes, nb, S, o, 0);
-  if (nb) k_dict_gather<<<(uint32_t)nb, kDThreads, 0, stream>>>(nb, block_log2, S, o);
+  k_dict_total<<<1, 64, 0, stream>>>(nb, S, 0);
+  if (nb)
+    k_dict_gather<<<(uint32_t)((nb + kDThreads / 64 - 1) / (kDThreads / 64)), kDThreads, 0,
+                    stream>>>(nb, block_log2, S, o);
   unsigned long long total = 0;
   uint32_t err = 0;
   if (hipMemcpyAsync(&total, S.total, 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
@@ -385,12 +391,18 @@ lcp_status lcp_dict_decode(const void* in, uint64_t size, void* out, uint64_t ou
   // the stream's sizes (at byte offset kDHdr), copied into scratch
   if (nb && hipMemcpyAsync(S.sizes, src + kDHdr, 4 * nb, hipMemcpyDeviceToDevice, stream) != hipSuccess)
     return LCP_ERR_DEVICE;
-  k_dict_offsets<<<1, kDThreads, 0, stream>>>(S.sizes, nb, S, nullptr, size);
+  if (nb) {
+    k_dict_widen<<<(uint32_t)((nb + kDThreads - 1) / kDThreads), kDThreads, 0, stream>>>(nb, S);
+    lcp::scan_device<uint64_t>(S.offs, nb, nullptr, true, S.tmp, stream);
+  }
+  k_dict_total<<<1, 64, 0, stream>>>(nb, S, size);
+  // an empty stream has no table (nothing to decode)
+  if (nb) k_dict_slots<<<kDM / 4 / kDThreads, kDThreads, 0, stream>>>(src, S);
   uint32_t err = 0;
   if (hipMemcpyAsync(&err, S.err, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess)
     return LCP_ERR_DEVICE;
-  if (err) return LCP_ERR_CORRUPT;  // the blocks would reach past the stream
+  if (err) return LCP_ERR_CORRUPT;  // blocks past the stream, or a table not summing to 4096
   if (nb)
     k_dict_decode<<<(uint32_t)((nb + kDLanes - 1) / kDLanes), kDLanes, 0, stream>>>(
         src, n, bl, nb, S, static_cast<uint8_t*>(out));
