@@ -626,7 +626,7 @@ def bench_next_rows(args, torch, lcp, frames, k, steps=2, n_random=16):
     # the dictionary stage (lcp_dict_*) over the float stream's records, then over
     # the records of frames that do not move (frame 0 eight times: every temporal
     # residual is zero, one Huffman bit per value); each stream decoded and checked
-    def dict_leg(recs, what, reps=3, bl=11):
+    def dict_leg(recs, what, reps=3, bl=16):
         nbytes = recs.numel()
         scr_e = torch.empty(lcp.dict_scratch_bytes(nbytes, bl, True), dtype=torch.uint8, device=dev)
         scr_d = torch.empty(lcp.dict_scratch_bytes(nbytes, bl, False), dtype=torch.uint8, device=dev)

@@ -1451,12 +1451,13 @@ int lco_search_k(const void* const* x, int F, uint64_t n, const lco_params* p, i
 }
 
 /* ------------------------------------------------------------------------
- * Dictionary stage: order-0 rANS over bytes (see lcp_oracle.h for the
- * stream).  Plain sequential code: one block after the other, one byte at a
- * time.
+ * Dictionary stage: order-0 rANS over bytes in blocks of 64 interleaved
+ * lanes (see lcp_oracle.h for the stream).  Plain sequential code: one block
+ * after the other, one lane after the other, one byte at a time.
  * ------------------------------------------------------------------------ */
 #define DICT_M (1u << LCO_DICT_SCALE)
 #define DICT_L (1u << 23)
+#define DICT_W 64
 #define DICT_HDR (4 + 4 + 8 + 2 * 256)
 
 static uint64_t dict_blocks(uint64_t n, int block_log2) {
@@ -1464,10 +1465,11 @@ static uint64_t dict_blocks(uint64_t n, int block_log2) {
 }
 
 uint64_t lco_dict_bound(uint64_t n, int block_log2) {
-  if (block_log2 < 8 || block_log2 > 20) return 0;
+  if (block_log2 < 12 || block_log2 > 20) return 0;
   const uint64_t nb = dict_blocks(n, block_log2);
-  /* a byte costs at most 12 bits (frequency 1 of 4096); a block adds its state */
-  return DICT_HDR + 4 * nb + n + n / 2 + 8 * nb;
+  /* a byte costs at most 12 bits (frequency 1 of 4096); a lane adds its state
+     and a byte of rounding, a block its table of lane sizes */
+  return DICT_HDR + 4 * nb + n + n / 2 + nb * (2 * DICT_W + 8 * DICT_W);
 }
 
 int lco_dict_normalise(const uint64_t* counts, uint16_t* freq) {
@@ -1514,10 +1516,9 @@ static uint32_t get32(const uint8_t* p) {
 
 int lco_dict_encode(const uint8_t* in, uint64_t n, int block_log2, uint8_t* out, uint64_t cap,
                     uint64_t* size) {
-  if ((n && !in) || !out || !size || block_log2 < 8 || block_log2 > 20) return LCO_ERR_ARG;
+  if ((n && !in) || !out || !size || block_log2 < 12 || block_log2 > 20) return LCO_ERR_ARG;
   const uint64_t B = 1ull << block_log2, nb = dict_blocks(n, block_log2);
-  const uint64_t need = lco_dict_bound(n, block_log2);
-  *size = need;
+  *size = lco_dict_bound(n, block_log2);
   if (cap < DICT_HDR + 4 * nb) return LCO_ERR_CAPACITY;
   uint64_t counts[256] = {0};
   for (uint64_t i = 0; i < n; i++) counts[in[i]]++;
@@ -1537,34 +1538,47 @@ int lco_dict_encode(const uint8_t* in, uint64_t n, int block_log2, uint8_t* out,
   }
   uint8_t* sizes = out + DICT_HDR;
   uint64_t pos = DICT_HDR + 4 * nb;
-  /* each block codes into a scratch buffer from its end, then is copied */
-  uint8_t* tmp = (uint8_t*)malloc(B + B / 2 + 8);
+  /* a lane codes into a scratch buffer from its end, then is copied */
+  const uint64_t lane_cap = (B / DICT_W) + (B / DICT_W) / 2 + 8;
+  uint8_t* tmp = (uint8_t*)malloc(lane_cap);
   if (!tmp) return LCO_ERR_BUDGET;
   for (uint64_t b = 0; b < nb; b++) {
     const uint64_t i0 = b * B, len = n - i0 < B ? n - i0 : B;
-    uint8_t* end = tmp + B + B / 2 + 8;
-    uint8_t* p = end;
-    uint32_t x = DICT_L;
-    for (uint64_t k = len; k-- > 0;) {
-      const uint32_t s = in[i0 + k], f = freq[s];
-      const uint32_t x_max = ((DICT_L >> LCO_DICT_SCALE) << 8) * f;
-      while (x >= x_max) {
-        *--p = (uint8_t)(x & 0xFF);
-        x >>= 8;
-      }
-      x = (x / f) * DICT_M + x % f + cum[s];
-    }
-    p -= 4;
-    put32(p, x);
-    const uint64_t csize = (uint64_t)(end - p);
-    put32(sizes + 4 * b, (uint32_t)csize);
-    if (pos + csize > cap) {
+    const uint64_t bpos = pos;
+    if (pos + 2 * DICT_W > cap) {
       free(tmp);
-      *size = pos + csize;
       return LCO_ERR_CAPACITY;
     }
-    memcpy(out + pos, p, csize);
-    pos += csize;
+    pos += 2 * DICT_W; /* the lanes' sizes, u16 each */
+    for (int k = 0; k < DICT_W; k++) {
+      uint8_t* end = tmp + lane_cap;
+      uint8_t* p = end;
+      uint32_t x = DICT_L;
+      /* lane k: bytes k, k + 64, ... of the block, from the last */
+      const uint64_t cnt = (uint64_t)k < len ? (len - (uint64_t)k + DICT_W - 1) / DICT_W : 0;
+      for (uint64_t m = cnt; m-- > 0;) {
+        const uint32_t s = in[i0 + (uint64_t)k + DICT_W * m], f = freq[s];
+        const uint32_t x_max = ((DICT_L >> LCO_DICT_SCALE) << 8) * f;
+        while (x >= x_max) {
+          *--p = (uint8_t)(x & 0xFF);
+          x >>= 8;
+        }
+        x = (x / f) * DICT_M + x % f + cum[s];
+      }
+      p -= 4;
+      put32(p, x);
+      const uint64_t lsize = (uint64_t)(end - p);
+      out[bpos + 2 * k] = (uint8_t)lsize;
+      out[bpos + 2 * k + 1] = (uint8_t)(lsize >> 8);
+      if (pos + lsize > cap) {
+        free(tmp);
+        *size = pos + lsize;
+        return LCO_ERR_CAPACITY;
+      }
+      memcpy(out + pos, p, lsize);
+      pos += lsize;
+    }
+    put32(sizes + 4 * b, (uint32_t)(pos - bpos));
   }
   free(tmp);
   *size = pos;
@@ -1575,7 +1589,7 @@ int lco_dict_decode(const uint8_t* in, uint64_t size, uint8_t* out, uint64_t cap
   if (!in || !n_out || size < DICT_HDR) return LCO_ERR_ARG;
   if (get32(in) != LCO_DICT_MAGIC) return LCO_ERR_CORRUPT;
   const int block_log2 = (int)get32(in + 4);
-  if (block_log2 < 8 || block_log2 > 20) return LCO_ERR_CORRUPT;
+  if (block_log2 < 12 || block_log2 > 20) return LCO_ERR_CORRUPT;
   const uint64_t n = (uint64_t)get32(in + 8) | (uint64_t)get32(in + 12) << 32;
   *n_out = n;
   const uint64_t B = 1ull << block_log2, nb = dict_blocks(n, block_log2);
@@ -1591,25 +1605,33 @@ int lco_dict_decode(const uint8_t* in, uint64_t size, uint8_t* out, uint64_t cap
   if (n && cum[256] != DICT_M) return LCO_ERR_CORRUPT;
   uint64_t pos = DICT_HDR + 4 * nb;
   for (uint64_t b = 0; b < nb; b++) {
-    const uint64_t csize = get32(in + DICT_HDR + 4 * b);
+    const uint64_t bsize = get32(in + DICT_HDR + 4 * b);
     const uint64_t i0 = b * B, len = n - i0 < B ? n - i0 : B;
-    if (csize < 4 || pos + csize > size) return LCO_ERR_CORRUPT;
-    const uint8_t* p = in + pos;
-    uint32_t x = get32(p);
-    uint64_t r = 4;
-    for (uint64_t k = 0; k < len; k++) {
-      const uint32_t slot = x & (DICT_M - 1);
-      int s = 0;
-      while (cum[s + 1] <= slot) s++; /* the byte whose interval holds the slot */
-      x = freq[s] * (x >> LCO_DICT_SCALE) + slot - cum[s];
-      while (x < DICT_L) {
-        if (r >= csize) return LCO_ERR_CORRUPT;
-        x = (x << 8) | p[r++];
+    if (bsize < 2 * DICT_W || pos + bsize > size) return LCO_ERR_CORRUPT;
+    uint64_t lpos = pos + 2 * DICT_W;
+    for (int k = 0; k < DICT_W; k++) {
+      const uint64_t lsize = (uint64_t)in[pos + 2 * k] | (uint64_t)in[pos + 2 * k + 1] << 8;
+      if (lsize < 4 || lpos + lsize > pos + bsize) return LCO_ERR_CORRUPT;
+      const uint8_t* p = in + lpos;
+      uint32_t x = get32(p);
+      uint64_t r = 4;
+      const uint64_t cnt = (uint64_t)k < len ? (len - (uint64_t)k + DICT_W - 1) / DICT_W : 0;
+      for (uint64_t m = 0; m < cnt; m++) {
+        const uint32_t slot = x & (DICT_M - 1);
+        int s = 0;
+        while (cum[s + 1] <= slot) s++; /* the byte whose interval holds the slot */
+        x = freq[s] * (x >> LCO_DICT_SCALE) + slot - cum[s];
+        while (x < DICT_L) {
+          if (r >= lsize) return LCO_ERR_CORRUPT;
+          x = (x << 8) | p[r++];
+        }
+        out[i0 + (uint64_t)k + DICT_W * m] = (uint8_t)s;
       }
-      out[i0 + k] = (uint8_t)s;
+      if (x != DICT_L || r != lsize) return LCO_ERR_CORRUPT;
+      lpos += lsize;
     }
-    if (x != DICT_L || r != csize) return LCO_ERR_CORRUPT;
-    pos += csize;
+    if (lpos != pos + bsize) return LCO_ERR_CORRUPT;
+    pos += bsize;
   }
   if (pos != size) return LCO_ERR_CORRUPT;
   return LCO_OK;

@@ -172,15 +172,17 @@ int lco_container_closure(const uint8_t* cont, uint64_t size, uint64_t k, uint64
 /* ---- dictionary stage (the last coding step, Sec. 6.2.2 and Sec. 7.1) ----
  * A lossless pass over coded bytes (records): an order-0 range-asymmetric
  * numeral system (rANS) coder over bytes with one frequency table for the
- * whole input and independent blocks of 2^block_log2 bytes.  Stream:
+ * whole input and independent blocks of 2^block_log2 bytes (12..20), each
+ * split among 64 interleaved lanes (lane k: the block's bytes k, k + 64, ...).
+ * Stream:
  *   u32 magic 0x4450434C, u32 block_log2, u64 n (input bytes),
  *   u16 freq[256] (normalised to 4096 when n > 0),
  *   u32 size[nb] (each block's coded bytes, nb = ceil(n / 2^block_log2)),
- *   then the blocks' coded bytes back to back.
- * A block codes its bytes from last to first with a 32-bit state that starts
+ *   then the blocks: u16 lane_size[64], then the 64 lanes' coded bytes.
+ * A lane codes its bytes from last to first with a 32-bit state that starts
  * at 2^23; a byte s with frequency f and cumulative frequency c takes the
  * state x to (x / f) * 4096 + x % f + c after the low bytes of x are written
- * out while x >= 2^19 f; the coded block is the final state (4 bytes,
+ * out while x >= 2^19 f; the coded lane is the final state (4 bytes,
  * little-endian) followed by the written bytes in the order a decoder reads
  * them.  Normalisation: f = max(1, floor(count * 4096 / n)) for every byte
  * value present; a shortfall goes to the most frequent value (ties: the

@@ -2,22 +2,22 @@
 // the paper fills with a general-purpose dictionary coder), here an order-0
 // range-asymmetric numeral system (rANS) coder over the bytes of coded
 // records.  One frequency table for the whole input (normalised to 4096) and
-// independent blocks of 2^block_log2 bytes, each coded by one lane: a block's
-// bytes go from last to first through a 32-bit state that starts at 2^23; a
-// byte s of frequency f and cumulative frequency c first writes out the low
-// bytes of the state while it is at least 2^19 f, then takes it to
-// (x / f) 4096 + x % f + c.  The coded block is the final state (4 bytes,
-// little-endian) followed by the written bytes in reading order.  Stream: u32
-// magic "LCPD", u32 block_log2, u64 n, u16 freq[256], u32 size[nb], then the
-// coded blocks back to back.
+// independent blocks of 2^block_log2 bytes, each coded by one wave whose lane
+// k takes the block's bytes k, k + 64, ... (so the lanes read and write
+// neighbouring bytes): a lane's bytes go from last to first through a 32-bit
+// state that starts at 2^23; a byte s of frequency f and cumulative frequency
+// c first writes out the low bytes of the state while it is at least 2^19 f,
+// then takes it to (x / f) 4096 + x % f + c.  A coded lane is the final state
+// (4 bytes, little-endian) followed by the written bytes in reading order.
+// Stream: u32 magic "LCPD", u32 block_log2, u64 n, u16 freq[256], u32
+// size[nb], then the blocks (u16 lane_size[64], then the lanes' bytes).
 //
 // Encode: byte histogram; the table (one thread: normalisation, header);
-// blocks coded into staging slots (each lane also writes its block's size
+// blocks coded into per-lane staging (each wave also writes its block's size
 // into the stream's size table); the sizes scanned into offsets (the
 // library's device scan); blocks gathered into the stream, a wave per block.
 // Decode: one header read-back, the sizes scanned and checked against the
-// stream's size, blocks decoded with the table and a 4096-entry slot-to-byte
-// map in LDS.
+// stream's size, the slot-to-byte map built once, blocks decoded a wave each.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -32,12 +32,16 @@ constexpr uint32_t kDM = 1u << kDScale;
 constexpr uint32_t kDL = 1u << 23;
 constexpr uint64_t kDHdr = 4 + 4 + 8 + 2 * 256;
 constexpr int kDThreads = 256;
-constexpr int kDLanes = 64;  // blocks per coding workgroup, one per lane
+constexpr int kDLanes = 64;  // lanes of a block (one wave)
 
 enum : uint32_t { kDErrCorrupt = 1u };
 
 __host__ __device__ inline uint64_t dict_blocks(uint64_t n, int bl) { return (n + (1ull << bl) - 1) >> bl; }
-__host__ __device__ inline uint64_t dict_slot(int bl) { return (((1ull << bl) + (1ull << bl) / 2 + 8) + 15) & ~15ull; }
+// a lane's staging: at most 1.5 bytes per byte, its state and a byte of rounding
+__host__ __device__ inline uint64_t dict_lane_cap(int bl) {
+  const uint64_t per = (1ull << bl) / kDLanes;
+  return (per + per / 2 + 8 + 15) & ~15ull;
+}
 
 // Scratch of one call (device, 256-byte aligned pieces).
 struct DictScratch {
@@ -50,7 +54,8 @@ struct DictScratch {
   uint32_t* err;               // [1]
   uint64_t* tmp;               // scan scratch
   uint32_t* sym;               // [4096 / 4] decode: the slot-to-byte map, four slots a word
-  uint8_t* stage;              // [nb][slot] (encode only)
+  uint32_t* lane;              // [nb][64] encode: the lanes' coded sizes
+  uint8_t* stage;              // [nb][64][lane_cap] (encode only)
 };
 uint64_t align256(uint64_t b) { return (b + 255) & ~255ull; }
 uint64_t dict_scratch(uint64_t nb, int bl, bool enc, DictScratch* S, uint8_t* base) {
@@ -70,7 +75,8 @@ uint64_t dict_scratch(uint64_t nb, int bl, bool enc, DictScratch* S, uint8_t* ba
   x.err = reinterpret_cast<uint32_t*>(take(4));
   x.tmp = reinterpret_cast<uint64_t*>(take(8 * lcp::scan_tmp_elems(nb + 1)));
   x.sym = reinterpret_cast<uint32_t*>(take(kDM));
-  x.stage = take(enc ? nb * dict_slot(bl) : 0);
+  x.lane = reinterpret_cast<uint32_t*>(take(enc ? 4 * kDLanes * nb : 0));
+  x.stage = take(enc ? nb * kDLanes * dict_lane_cap(bl) : 0);
   if (S) *S = x;
   return o;
 }
@@ -149,8 +155,18 @@ __global__ void k_dict_table(uint64_t n, int bl, DictScratch S, uint8_t* out) {
   }
 }
 
-// One block per lane, coded from its last byte to its first into the end of
-// its staging slot (at most 1.5 bytes per byte plus the state fit the slot).
+__device__ inline uint32_t wave_excl_sum(uint32_t v) {
+  uint32_t incl = v;
+#pragma unroll
+  for (int d = 1; d < kDLanes; d <<= 1) {
+    const uint32_t o = (uint32_t)__shfl_up((int)incl, d, kDLanes);
+    if ((int)(threadIdx.x % kDLanes) >= d) incl += o;
+  }
+  return incl - v;
+}
+
+// One block per wave (workgroup of 64): lane k codes the block's bytes k,
+// k + 64, ... from the last into the end of its staging region.
 __global__ __launch_bounds__(kDLanes) void k_dict_encode(const uint8_t* in, uint64_t n, int bl,
                                                          uint64_t nb, DictScratch S,
                                                          uint8_t* out) {
@@ -160,39 +176,51 @@ __global__ __launch_bounds__(kDLanes) void k_dict_encode(const uint8_t* in, uint
     cum[s] = S.cum[s];
   }
   __syncthreads();
-  const uint64_t b = (uint64_t)blockIdx.x * kDLanes + threadIdx.x;
-  if (b >= nb) return;
-  const uint64_t B = 1ull << bl, slot = dict_slot(bl);
+  const uint64_t b = blockIdx.x;
+  const uint32_t k = threadIdx.x;
+  const uint64_t B = 1ull << bl, cap = dict_lane_cap(bl);
   const uint64_t i0 = b * B, len = n - i0 < B ? n - i0 : B;
-  uint8_t* const lo = S.stage + b * slot;
-  uint8_t* const end = lo + slot;
+  const uint64_t cnt = k < len ? (len - k + kDLanes - 1) / kDLanes : 0;
+  uint8_t* const lo = S.stage + (b * kDLanes + k) * cap;
+  uint8_t* const end = lo + cap;
   uint8_t* p = end;
   uint32_t x = kDL;
-  for (uint64_t k = len; k-- > 0;) {
-    const uint32_t s = in[i0 + k], f = freq[s];
+  bool over = false;
+  for (uint64_t m = cnt; m-- > 0 && !over;) {
+    const uint32_t s = in[i0 + k + kDLanes * m], f = freq[s];
     const uint32_t x_max = ((kDL >> kDScale) << 8) * f;
     while (x >= x_max) {
-      if (p - lo <= 4) {  // never taken: a block codes into at most 1.5 bytes per byte + 5
-        S.sizes[b] = 0;
-        S.offs[b] = 0;
-        reinterpret_cast<uint32_t*>(out + kDHdr)[b] = 0;
-        atomicOr(S.err, kDErrCorrupt);
-        return;
+      if (p - lo <= 4) {  // never taken: a lane codes into at most 1.5 bytes per byte + 5
+        over = true;
+        break;
       }
       *--p = (uint8_t)(x & 0xFFu);
       x >>= 8;
     }
     x = (x / f) * kDM + x % f + cum[s];
   }
-  p -= 4;
-  p[0] = (uint8_t)x;
-  p[1] = (uint8_t)(x >> 8);
-  p[2] = (uint8_t)(x >> 16);
-  p[3] = (uint8_t)(x >> 24);
-  const uint32_t size = (uint32_t)(end - p);
-  S.sizes[b] = size;
-  S.offs[b] = size;
-  reinterpret_cast<uint32_t*>(out + kDHdr)[b] = size;  // the stream's size table (4-byte aligned)
+  uint32_t size = 0;
+  if (!over) {
+    p -= 4;
+    p[0] = (uint8_t)x;
+    p[1] = (uint8_t)(x >> 8);
+    p[2] = (uint8_t)(x >> 16);
+    p[3] = (uint8_t)(x >> 24);
+    size = (uint32_t)(end - p);
+  } else {
+    atomicOr(S.err, kDErrCorrupt);
+  }
+  S.lane[b * kDLanes + k] = size;
+  // the block's size: the lanes' table and their bytes
+  uint32_t tot = size;
+#pragma unroll
+  for (int d = kDLanes / 2; d > 0; d >>= 1) tot += (uint32_t)__shfl_xor((int)tot, d, kDLanes);
+  if (k == 0) {
+    const uint32_t bsize = 2 * kDLanes + tot;
+    S.sizes[b] = bsize;
+    S.offs[b] = bsize;
+    reinterpret_cast<uint32_t*>(out + kDHdr)[b] = bsize;  // the stream's size table
+  }
 }
 
 // The block sizes as u64 (decoding: from the stream), to be scanned in place.
@@ -212,15 +240,26 @@ __global__ void k_dict_total(uint64_t nb, DictScratch S, uint64_t check_total) {
   if (check_total && total != check_total) atomicOr(S.err, kDErrCorrupt);
 }
 
-// Coded blocks from their staging slots into the stream, one workgroup each.
+// Coded blocks into the stream, a wave per block: the lanes' size table, then
+// each lane's bytes copied by the whole wave in turn.
 __global__ __launch_bounds__(kDThreads) void k_dict_gather(uint64_t nb, int bl, DictScratch S,
                                                            uint8_t* out) {
-  const uint64_t b = (uint64_t)blockIdx.x * (kDThreads / 64) + threadIdx.x / 64;
+  const uint64_t b = (uint64_t)blockIdx.x * (kDThreads / kDLanes) + threadIdx.x / kDLanes;
   if (b >= nb) return;
-  const uint64_t slot = dict_slot(bl), size = S.sizes[b];
-  const uint8_t* src = S.stage + b * slot + slot - size;
+  const uint32_t k = threadIdx.x % kDLanes;
+  const uint64_t cap = dict_lane_cap(bl);
+  const uint32_t size = S.lane[b * kDLanes + k];
+  const uint32_t off = wave_excl_sum(size);
   uint8_t* dst = out + kDHdr + 4 * nb + S.offs[b];
-  for (uint64_t i = threadIdx.x % 64; i < size; i += 64) dst[i] = src[i];
+  dst[2 * k] = (uint8_t)size;
+  dst[2 * k + 1] = (uint8_t)(size >> 8);
+  for (uint32_t j = 0; j < kDLanes; j++) {
+    const uint32_t sj = (uint32_t)__shfl((int)size, (int)j, kDLanes);
+    const uint32_t oj = (uint32_t)__shfl((int)off, (int)j, kDLanes);
+    const uint8_t* src = S.stage + (b * kDLanes + j) * cap + cap - sj;
+    uint8_t* d = dst + 2 * kDLanes + oj;
+    for (uint32_t i = k; i < sj; i += kDLanes) d[i] = src[i];
+  }
 }
 
 // The slot-to-byte map of a stream's table (slot i belongs to the byte whose
@@ -255,10 +294,12 @@ __global__ __launch_bounds__(kDThreads) void k_dict_slots(const uint8_t* in, Dic
   S.sym[w] = packed;
 }
 
-// One block per lane: the state read from the block's first four bytes, then
-// per byte the slot x mod 4096 names the byte, the state steps back and takes
-// in bytes while it is below 2^23.  A block must end on the initial state and
-// use exactly its bytes.
+// One block per wave: lane k finds its bytes through the block's lane sizes,
+// reads its state from their first four, then per byte the slot x mod 4096
+// names the byte, the state steps back and takes in bytes while it is below
+// 2^23; the byte goes to the block's position k + 64 m.  Every lane must end
+// on the initial state with all its bytes used, and the lanes' sizes must
+// fill the block.
 __global__ __launch_bounds__(kDLanes) void k_dict_decode(const uint8_t* in, uint64_t n, int bl,
                                                          uint64_t nb, DictScratch S,
                                                          uint8_t* out) {
@@ -278,35 +319,50 @@ __global__ __launch_bounds__(kDLanes) void k_dict_decode(const uint8_t* in, uint
     cum[256] = c;
   }
   __syncthreads();
-  const uint64_t b = (uint64_t)blockIdx.x * kDLanes + threadIdx.x;
-  if (b >= nb) return;
+  const uint64_t b = blockIdx.x;
+  const uint32_t k = threadIdx.x;
   const uint64_t B = 1ull << bl;
   const uint64_t i0 = b * B, len = n - i0 < B ? n - i0 : B;
-  const uint64_t csize = S.sizes[b];
-  const uint8_t* p = in + kDHdr + 4 * nb + S.offs[b];
-  if (csize < 4) {
+  const uint64_t bsize = S.sizes[b];
+  const uint8_t* blk = in + kDHdr + 4 * nb + S.offs[b];
+  if (bsize < 2 * kDLanes) {  // the whole wave sees the same size
+    if (k == 0) atomicOr(S.err, kDErrCorrupt);
+    return;
+  }
+  const uint32_t lsize = (uint32_t)blk[2 * k] | (uint32_t)blk[2 * k + 1] << 8;
+  const uint32_t loff = wave_excl_sum(lsize);
+  uint32_t tot = lsize;
+#pragma unroll
+  for (int d = kDLanes / 2; d > 0; d >>= 1) tot += (uint32_t)__shfl_xor((int)tot, d, kDLanes);
+  if ((uint64_t)tot + 2 * kDLanes != bsize) {
+    if (k == 0) atomicOr(S.err, kDErrCorrupt);
+    return;
+  }
+  if (lsize < 4) {
     atomicOr(S.err, kDErrCorrupt);
     return;
   }
+  const uint8_t* p = blk + 2 * kDLanes + loff;
+  const uint64_t cnt = k < len ? (len - k + kDLanes - 1) / kDLanes : 0;
   uint32_t x = (uint32_t)p[0] | (uint32_t)p[1] << 8 | (uint32_t)p[2] << 16 | (uint32_t)p[3] << 24;
-  uint64_t r = 4;
-  for (uint64_t k = 0; k < len; k++) {
+  uint32_t r = 4;
+  for (uint64_t m = 0; m < cnt; m++) {
     const uint32_t slot = x & (kDM - 1);
     const uint32_t s = sym[slot];
     x = freq[s] * (x >> kDScale) + slot - cum[s];
     while (x < kDL) {
-      if (r >= csize) {
+      if (r >= lsize) {
         atomicOr(S.err, kDErrCorrupt);
         return;
       }
       x = (x << 8) | p[r++];
     }
-    out[i0 + k] = (uint8_t)s;
+    out[i0 + k + kDLanes * m] = (uint8_t)s;
   }
-  if (x != kDL || r != csize) atomicOr(S.err, kDErrCorrupt);
+  if (x != kDL || r != lsize) atomicOr(S.err, kDErrCorrupt);
 }
 
-lcp_status dict_args(int bl) { return bl < 8 || bl > 20 ? LCP_ERR_ARG : LCP_OK; }
+lcp_status dict_args(int bl) { return bl < 12 || bl > 20 ? LCP_ERR_ARG : LCP_OK; }
 
 }  // namespace
 
@@ -315,7 +371,7 @@ extern "C" {
 uint64_t lcp_dict_bound(uint64_t n, int block_log2) {
   if (dict_args(block_log2)) return 0;
   const uint64_t nb = dict_blocks(n, block_log2);
-  return kDHdr + 4 * nb + n + n / 2 + 8 * nb;
+  return kDHdr + 4 * nb + n + n / 2 + nb * (2 * kDLanes + 8 * kDLanes);
 }
 
 lcp_status lcp_dict_scratch_bytes(uint64_t n, int block_log2, int encode, uint64_t* device_bytes) {
@@ -348,14 +404,13 @@ lcp_status lcp_dict_encode(const void* in, uint64_t n, int block_log2, void* out
   }
   k_dict_table<<<1, 64, 0, stream>>>(n, block_log2, S, o);
   if (nb) {
-    k_dict_encode<<<(uint32_t)((nb + kDLanes - 1) / kDLanes), kDLanes, 0, stream>>>(
-        src, n, block_log2, nb, S, o);
+    k_dict_encode<<<(uint32_t)nb, kDLanes, 0, stream>>>(src, n, block_log2, nb, S, o);
     lcp::scan_device<uint64_t>(S.offs, nb, nullptr, true, S.tmp, stream);
   }
   k_dict_total<<<1, 64, 0, stream>>>(nb, S, 0);
   if (nb)
-    k_dict_gather<<<(uint32_t)((nb + kDThreads / 64 - 1) / (kDThreads / 64)), kDThreads, 0,
-                    stream>>>(nb, block_log2, S, o);
+    k_dict_gather<<<(uint32_t)((nb + kDThreads / kDLanes - 1) / (kDThreads / kDLanes)), kDThreads,
+                    0, stream>>>(nb, block_log2, S, o);
   unsigned long long total = 0;
   uint32_t err = 0;
   if (hipMemcpyAsync(&total, S.total, 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
@@ -404,8 +459,8 @@ lcp_status lcp_dict_decode(const void* in, uint64_t size, void* out, uint64_t ou
     return LCP_ERR_DEVICE;
   if (err) return LCP_ERR_CORRUPT;  // blocks past the stream, or a table not summing to 4096
   if (nb)
-    k_dict_decode<<<(uint32_t)((nb + kDLanes - 1) / kDLanes), kDLanes, 0, stream>>>(
-        src, n, bl, nb, S, static_cast<uint8_t*>(out));
+    k_dict_decode<<<(uint32_t)nb, kDLanes, 0, stream>>>(src, n, bl, nb, S,
+                                                       static_cast<uint8_t*>(out));
   if (hipMemcpyAsync(&err, S.err, 4, hipMemcpyDeviceToHost, stream) != hipSuccess ||
       hipStreamSynchronize(stream) != hipSuccess)
     return LCP_ERR_DEVICE;

@@ -53,8 +53,8 @@ def round_trip(lcp, data: np.ndarray, bl: int):
 
 
 @pytest.mark.parametrize("kind", ["skewed", "uniform", "runs", "constant"])
-@pytest.mark.parametrize("n,bl", [(1, 8), (4097, 12), (65_536 * 3 + 17, 12), (300_001, 16),
-                                  (5_000, 8)])
+@pytest.mark.parametrize("n,bl", [(1, 12), (4097, 12), (65_536 * 3 + 17, 12), (300_001, 16),
+                                  (5_000, 13), (200_000, 20)])
 def test_dict_parity(lcp, kind, n, bl):
     round_trip(lcp, sample(kind, n, n + bl), bl)
 

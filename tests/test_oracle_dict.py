@@ -41,47 +41,54 @@ def test_normalise_hand_cases():
     assert O.dict_normalise(np.zeros(256, np.uint64)).sum() == 0
 
 
+LANES = 64
+STATE = bytes([0x00, 0x00, 0x80, 0x00])  # 2^23, little-endian
+BLOCK_CONST = (4).to_bytes(2, "little") * LANES + STATE * LANES
+
+
 def test_constant_block_closed_form():
-    # one value at frequency 4096: x -> (x / 4096) * 4096 + x % 4096 = x, so the
-    # state stays at 2^23 and no byte is written; the block is the state alone
+    # one value at frequency 4096: x -> (x / 4096) * 4096 + x % 4096 = x, so every
+    # lane's state stays at 2^23 and no byte is written; a block is 64 lane sizes
+    # of 4 and 64 states (lanes without bytes keep the initial state too)
     for n in (1, 300, 4096):
         st = O.dict_encode(bytes([0x5A]) * n, block_log2=12)
-        assert len(st) == HDR + 4 + 4
+        assert len(st) == HDR + 4 + len(BLOCK_CONST)
         assert st[:4] == (0x4450434C).to_bytes(4, "little")
         assert int.from_bytes(st[8:16], "little") == n
         assert int.from_bytes(st[16 + 2 * 0x5A:18 + 2 * 0x5A], "little") == 4096
-        assert st[HDR:HDR + 4] == (4).to_bytes(4, "little")
-        assert st[HDR + 4:] == bytes([0x00, 0x00, 0x80, 0x00])
-    # and the hand-built stream decodes to the block
+        assert st[HDR:HDR + 4] == len(BLOCK_CONST).to_bytes(4, "little")
+        assert st[HDR + 4:] == BLOCK_CONST
+    # and the hand-built stream (two blocks) decodes to the bytes
     hand = bytearray(HDR + 8)
     hand[0:4] = (0x4450434C).to_bytes(4, "little")
     hand[4:8] = (12).to_bytes(4, "little")
-    hand[8:16] = (37).to_bytes(8, "little")
+    hand[8:16] = (4096 + 37).to_bytes(8, "little")
     hand[16 + 2 * 3:18 + 2 * 3] = (4096).to_bytes(2, "little")
-    hand[HDR:HDR + 4] = (4).to_bytes(4, "little")
-    hand[HDR + 4:] = bytes([0x00, 0x00, 0x80, 0x00])
-    assert O.dict_decode(bytes(hand)) == bytes([3]) * 37
+    hand[HDR:HDR + 4] = len(BLOCK_CONST).to_bytes(4, "little")
+    hand[HDR + 4:HDR + 8] = len(BLOCK_CONST).to_bytes(4, "little")
+    hand += BLOCK_CONST * 2
+    assert O.dict_decode(bytes(hand)) == bytes([3]) * (4096 + 37)
 
 
 def test_coding_cost_is_the_table_cross_entropy():
     # rANS codes a byte of frequency f in log2(4096 / f) bits up to the state's
-    # few bytes per block: the payload is that sum over the input, within 4
-    # bytes of state and 1 byte of rounding per block
+    # few bytes per lane: the payload is that sum over the input, within 4
+    # bytes of state and 1 byte of rounding per lane (and the lanes' sizes)
     rng = np.random.default_rng(1)
-    for p, n, bl in (([0.75, 0.125, 0.125], 300_000, 12), ([0.5] + [0.5 / 40] * 40, 123_457, 10)):
+    for p, n, bl in (([0.75, 0.125, 0.125], 300_000, 14), ([0.5] + [0.5 / 40] * 40, 123_457, 12)):
         data = rng.choice(len(p), size=n, p=p).astype(np.uint8)
         st = O.dict_encode(data.tobytes(), block_log2=bl)
         freq = np.frombuffer(st[16:HDR], np.uint16).astype(np.float64)
         counts = np.bincount(data, minlength=256)
         bits = sum(counts[s] * math.log2(4096 / freq[s]) for s in range(256) if counts[s])
         nb = (n + (1 << bl) - 1) >> bl
-        payload = len(st) - HDR - 4 * nb
-        assert abs(payload - bits / 8) <= 5 * nb, (payload, bits / 8)
+        payload = len(st) - HDR - 4 * nb - 2 * LANES * nb
+        assert abs(payload - bits / 8) <= 5 * LANES * nb, (payload, bits / 8)
         assert O.dict_decode(st) == data.tobytes()
 
 
-@pytest.mark.parametrize("n,bl", [(0, 12), (1, 8), (255, 8), (256, 8), (257, 8), (70_001, 12),
-                                  (1 << 16, 16)])
+@pytest.mark.parametrize("n,bl", [(0, 12), (1, 12), (63, 12), (64, 12), (65, 12), (4097, 12),
+                                  (70_001, 12), (1 << 16, 16), (300_001, 13)])
 def test_round_trip_ragged_blocks(n, bl):
     rng = np.random.default_rng(n + bl)
     # runs of one value, a skewed range and uniform bytes, one after the other
@@ -101,12 +108,12 @@ def test_uniform_bytes_cost_eight_bits():
     # 256 values of frequency 16 each: 8 bits per byte
     data = np.random.default_rng(3).permutation(np.repeat(np.arange(256, dtype=np.uint8), 64))
     st = O.dict_encode(data.tobytes(), block_log2=14)
-    assert abs((len(st) - HDR - 4) - len(data)) <= 5
+    assert abs((len(st) - HDR - 4 - 2 * LANES) - len(data)) <= 5 * LANES
 
 
 def test_stream_checks():
     data = bytes(np.random.default_rng(4).integers(0, 5, 5000, dtype=np.uint8))
-    st = bytearray(O.dict_encode(data, block_log2=10))
+    st = bytearray(O.dict_encode(data, block_log2=12))
     with pytest.raises(O.OracleError):
         O.dict_decode(bytes(st[:-1]))  # a block cut short
     bad = bytearray(st)
