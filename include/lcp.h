@@ -349,14 +349,16 @@ void lcp_container_close(lcp_container_t c);
  * (Sec. 7.1), which the paper fills with a general-purpose dictionary coder:
  * here a lossless pass over any coded bytes (typically the records of a
  * compress call), an order-0 rANS coder over bytes with one frequency table
- * for the input and independent blocks of 2^block_log2 bytes (8..20), one
- * block per GPU lane.  Stream: u32 magic "LCPD", u32 block_log2, u64 n,
- * u16 freq[256] (normalised to 4096), u32 size[nb] (nb = ceil(n / 2^block_log2)),
- * then the coded blocks.  A block is coded from its last byte to its first
- * through a 32-bit state starting at 2^23: a byte of frequency f and
- * cumulative frequency c writes out the state's low bytes while it is at least
- * 2^19 f, then takes it to (x / f) 4096 + x % f + c; the coded block is the
- * final state (4 bytes, little-endian) and the written bytes in reading order.
+ * for the input and independent blocks of 2^block_log2 bytes (12..20), one
+ * block per GPU wave whose lane k takes the block's bytes k, k + 64, ...
+ * Stream: u32 magic "LCPD", u32 block_log2, u64 n, u16 freq[256] (normalised
+ * to 4096), u32 size[nb] (nb = ceil(n / 2^block_log2)), then the blocks, each
+ * u16 lane_size[64] and the lanes' coded bytes.  A lane is coded from its last
+ * byte to its first through a 32-bit state starting at 2^23: a byte of
+ * frequency f and cumulative frequency c writes out the state's low bytes
+ * while it is at least 2^19 f, then takes it to (x / f) 4096 + x % f + c; the
+ * coded lane is the final state (4 bytes, little-endian) and the written bytes
+ * in reading order.
  *
  * lcp_dict_bound: the largest stream for n input bytes (0 for an invalid
  * block_log2).  lcp_dict_scratch_bytes: the device scratch an encode (encode
@@ -370,8 +372,9 @@ void lcp_container_close(lcp_container_t c);
  * lcp_dict_decode: a stream of size bytes (device) to out (device, out_cap
  * bytes); *n_out (host) receives n.  Synchronises the stream (twice).  Errors:
  * LCP_ERR_ARG, LCP_ERR_CORRUPT (a stream that fails its checks: magic, table
- * sum, sizes that do not add up to the stream, a block that does not end on
- * its initial state with all its bytes used), LCP_ERR_CAPACITY (*n_out = n),
+ * sum, block sizes that do not add up to the stream or lane sizes to their
+ * block, a lane that does not end on its initial state with all its bytes
+ * used), LCP_ERR_CAPACITY (*n_out = n),
  * LCP_ERR_BUDGET, LCP_ERR_DEVICE. */
 uint64_t lcp_dict_bound(uint64_t n, int block_log2);
 lcp_status lcp_dict_scratch_bytes(uint64_t n, int block_log2, int encode, uint64_t* device_bytes);
