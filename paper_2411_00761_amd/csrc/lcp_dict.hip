@@ -109,50 +109,60 @@ __global__ __launch_bounds__(kDThreads) void k_dict_hist(const uint8_t* in, uint
   if (bins[threadIdx.x]) atomicAdd(&S.counts[threadIdx.x], (unsigned long long)bins[threadIdx.x]);
 }
 
-// The table and the stream header, by one thread (256 values).
-__global__ void k_dict_table(uint64_t n, int bl, DictScratch S, uint8_t* out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  uint32_t f[256];
-  int64_t sum = 0;
-  for (int s = 0; s < 256; s++) {
-    const unsigned long long c = S.counts[s];
-    f[s] = 0;
-    if (c) {
-      // c * 4096 / n without overflow: c < 2^52 for any input below 2^52 bytes
-      const unsigned long long q = (c << kDScale) / n;
-      f[s] = q < 1 ? 1u : (uint32_t)q;
-      sum += f[s];
-    }
+// The table and the stream header: one workgroup, a thread per byte value;
+// the rare excess (many values rounded up to 1) is taken off by one thread.
+__global__ __launch_bounds__(kDThreads) void k_dict_table(uint64_t n, int bl, DictScratch S,
+                                                          uint8_t* out) {
+  __shared__ uint32_t f[256];
+  __shared__ unsigned long long red[kDThreads];
+  const uint32_t t = threadIdx.x;
+  const unsigned long long c = S.counts[t];
+  // c * 4096 / n without overflow: c < 2^52 for any input below 2^52 bytes
+  const unsigned long long q = c ? (c << kDScale) / n : 0ull;
+  f[t] = c ? (q < 1 ? 1u : (uint32_t)q) : 0u;
+  red[t] = f[t];
+  __syncthreads();
+  for (int d = kDThreads / 2; d > 0; d >>= 1) {
+    if ((int)t < d) red[t] += red[t + d];
+    __syncthreads();
   }
+  const int64_t sum = (int64_t)red[0];
+  __syncthreads();
   if (n && sum < (int64_t)kDM) {
-    int best = -1;
-    for (int s = 0; s < 256; s++)
-      if (S.counts[s] && (best < 0 || S.counts[s] > S.counts[best])) best = s;
-    f[best] += (uint32_t)((int64_t)kDM - sum);
+    // the most frequent value, ties to the smaller: (count, 255 - value) maximised
+    red[t] = c ? (c << 8) | (255u - t) : 0ull;
+    __syncthreads();
+    for (int d = kDThreads / 2; d > 0; d >>= 1) {
+      if ((int)t < d && red[t + d] > red[t]) red[t] = red[t + d];
+      __syncthreads();
+    }
+    if (t == 0) f[255u - (uint32_t)(red[0] & 255u)] += (uint32_t)((int64_t)kDM - sum);
+    __syncthreads();
   }
-  int64_t excess = n ? sum - (int64_t)kDM : 0;
-  while (excess > 0) {
-    int best = -1;
-    for (int s = 0; s < 256; s++)
-      if (f[s] > 1 && (best < 0 || f[s] > f[best])) best = s;
-    if (best < 0) break;  // not reachable: 256 values of at least 1 sum below 4096
-    const int64_t d = (int64_t)(f[best] - 1) < excess ? (int64_t)(f[best] - 1) : excess;
-    f[best] -= (uint32_t)d;
-    excess -= d;
+  if (t == 0) {
+    int64_t excess = n ? sum - (int64_t)kDM : 0;
+    while (excess > 0) {
+      int best = -1;
+      for (int s = 0; s < 256; s++)
+        if (f[s] > 1 && (best < 0 || f[s] > f[best])) best = s;
+      if (best < 0) break;  // not reachable: 256 values of at least 1 sum below 4096
+      const int64_t d = (int64_t)(f[best] - 1) < excess ? (int64_t)(f[best] - 1) : excess;
+      f[best] -= (uint32_t)d;
+      excess -= d;
+    }
+    uint32_t run = 0;
+    for (int s = 0; s < 256; s++) {
+      S.cum[s] = run;
+      run += f[s];
+    }
+    S.cum[256] = run;
+    const uint32_t head[4] = {kDMagic, (uint32_t)bl, (uint32_t)n, (uint32_t)(n >> 32)};
+    for (int i = 0; i < 16; i++) out[i] = (uint8_t)(head[i / 4] >> (8 * (i % 4)));
   }
-  uint32_t c = 0;
-  for (int s = 0; s < 256; s++) {
-    S.freq[s] = f[s];
-    S.cum[s] = c;
-    c += f[s];
-  }
-  S.cum[256] = c;
-  const uint32_t head[4] = {kDMagic, (uint32_t)bl, (uint32_t)n, (uint32_t)(n >> 32)};
-  for (int i = 0; i < 16; i++) out[i] = (uint8_t)(head[i / 4] >> (8 * (i % 4)));
-  for (int s = 0; s < 256; s++) {
-    out[16 + 2 * s] = (uint8_t)f[s];
-    out[17 + 2 * s] = (uint8_t)(f[s] >> 8);
-  }
+  __syncthreads();
+  S.freq[t] = f[t];
+  out[16 + 2 * t] = (uint8_t)f[t];
+  out[17 + 2 * t] = (uint8_t)(f[t] >> 8);
 }
 
 __device__ inline uint32_t wave_excl_sum(uint32_t v) {
@@ -258,7 +268,15 @@ __global__ __launch_bounds__(kDThreads) void k_dict_gather(uint64_t nb, int bl, 
     const uint32_t oj = (uint32_t)__shfl((int)off, (int)j, kDLanes);
     const uint8_t* src = S.stage + (b * kDLanes + j) * cap + cap - sj;
     uint8_t* d = dst + 2 * kDLanes + oj;
-    for (uint32_t i = k; i < sj; i += kDLanes) d[i] = src[i];
+    // four bytes per lane requested together
+    for (uint32_t i = k; i < sj; i += 4 * kDLanes) {
+      uint8_t v[4];
+#pragma unroll
+      for (int u = 0; u < 4; u++) v[u] = i + u * kDLanes < sj ? src[i + u * kDLanes] : 0;
+#pragma unroll
+      for (int u = 0; u < 4; u++)
+        if (i + u * kDLanes < sj) d[i + u * kDLanes] = v[u];
+    }
   }
 }
 
@@ -402,7 +420,7 @@ lcp_status lcp_dict_encode(const void* in, uint64_t n, int block_log2, void* out
     k_dict_hist<<<(uint32_t)(hb < 1 ? 1 : (hb > 4096 ? 4096 : hb)), kDThreads, 0, stream>>>(src, n,
                                                                                             S);
   }
-  k_dict_table<<<1, 64, 0, stream>>>(n, block_log2, S, o);
+  k_dict_table<<<1, kDThreads, 0, stream>>>(n, block_log2, S, o);
   if (nb) {
     k_dict_encode<<<(uint32_t)nb, kDLanes, 0, stream>>>(src, n, block_log2, nb, S, o);
     lcp::scan_device<uint64_t>(S.offs, nb, nullptr, true, S.tmp, stream);

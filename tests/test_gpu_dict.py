@@ -107,3 +107,22 @@ def test_dict_refusals(lcp):
         lcp.dict_decode(out, size, len(data), out=torch.empty(10, dtype=torch.uint8,
                                                                device="cuda"))
     assert e.value.status == lcp.ERR_CAPACITY
+
+
+def test_dict_table_rules(lcp):
+    """The normalisation's special rules on the GPU: a shortfall on a tie goes to
+    the smaller value, an excess from many rare values comes off the largest
+    frequency (the tables the oracle's pins work by hand)."""
+    tie = np.array([5, 9, 2], np.uint8)
+    round_trip(lcp, tie, 12)
+    excess = np.concatenate([np.zeros(10_000, np.uint8), np.arange(1, 201, dtype=np.uint8)])
+    excess = np.random.default_rng(9).permutation(excess)
+    round_trip(lcp, excess, 12)
+    # the stream's tables are the hand-worked ones
+    out, size = lcp.dict_encode(torch.from_numpy(np.concatenate([tie, np.zeros(1, np.uint8)])).cuda(),
+                                n=3, block_log2=12)
+    f = np.frombuffer(out[16:16 + 512].cpu().numpy().tobytes(), np.uint16)
+    assert (f[2], f[5], f[9]) == (1366, 1365, 1365)
+    out, size = lcp.dict_encode(torch.from_numpy(excess).cuda(), block_log2=12)
+    f = np.frombuffer(out[16:16 + 512].cpu().numpy().tobytes(), np.uint16)
+    assert f[0] == 4015 - 119 and (f[1:201] == 1).all()
